@@ -1,0 +1,89 @@
+"""Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
+
+This module holds no arithmetic of the method: only a counter-based random
+number generator, the coarse structured triangulation handed to the solver
+as its input mesh, and the seeded data arrays built from the generator.
+
+Random numbers (counter mode splitmix64, Steele, Lea & Flood 2014):
+  key = seed*16 + stream;  x = (key << 32) + i;
+  out = splitmix64-finaliser(x + 0x9E3779B97F4A7C15);
+  uniform[0,1) = (out >> 11) * 2^-53;   uniform[-1,1) = 2u - 1.
+Data arrays are indexed C-order [nrhs][n_cells][n_qp][dim], and element i of
+that flat array takes counter i.
+"""
+import numpy as np
+
+_M64 = np.uint64(0xFFFFFFFFFFFFFFFF)
+_GOLD = np.uint64(0x9E3779B97F4A7C15)
+_C1 = np.uint64(0xBF58476D1CE4E5B9)
+_C2 = np.uint64(0x94D049BB133111EB)
+
+
+def splitmix64(seed, stream, idx):
+    """Counter-mode splitmix64 outputs (uint64) for counters ``idx``."""
+    idx = np.asarray(idx, dtype=np.uint64)
+    key = np.uint64(seed) * np.uint64(16) + np.uint64(stream)
+    with np.errstate(over="ignore"):
+        z = (key << np.uint64(32)) + idx + _GOLD
+        z = (z ^ (z >> np.uint64(30))) * _C1
+        z = (z ^ (z >> np.uint64(27))) * _C2
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def uniform01(seed, stream, n):
+    """n uniforms in [0,1) from counters 0..n-1."""
+    z = splitmix64(seed, stream, np.arange(n, dtype=np.uint64))
+    return (z >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+
+
+def uniform_pm1(seed, stream, shape):
+    """Uniforms in [-1,1) filling ``shape`` in C order."""
+    n = int(np.prod(shape))
+    return (2.0 * uniform01(seed, stream, n) - 1.0).reshape(shape)
+
+
+def normal(seed, stream, n):
+    """Standard normals by Box-Muller on (1-u1, u2); u1, u2 from streams
+    ``stream`` and ``stream+1``."""
+    u1 = 1.0 - uniform01(seed, stream, n)
+    u2 = uniform01(seed, stream + 1, n)
+    return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+
+
+def kuhn_square(n):
+    """Structured triangulation of [0,1]^2 with n x n squares, each split along
+    its (i,j)-(i+1,j+1) diagonal.
+
+    Vertex (i,j) has index i + (n+1) j.  Square (i,j) (index i + n j) yields two
+    triangles, in this order: (v_ij, v_i+1,j, v_i+1,j+1) then
+    (v_ij, v_i,j+1, v_i+1,j+1).  Returns (coords [nv,2] float64,
+    cells [nc,3] int32).
+    """
+    xs = np.linspace(0.0, 1.0, n + 1)
+    X, Y = np.meshgrid(xs, xs, indexing="xy")
+    coords = np.stack([X.ravel(), Y.ravel()], axis=1)
+    cells = []
+    for j in range(n):
+        for i in range(n):
+            v = lambda a, b: a + (n + 1) * b
+            cells.append((v(i, j), v(i + 1, j), v(i + 1, j + 1)))
+            cells.append((v(i, j), v(i, j + 1), v(i + 1, j + 1)))
+    return coords, np.asarray(cells, dtype=np.int32)
+
+
+def source_uniform(seed, nrhs, n_cells, n_qp, dim=2, stream=0):
+    """f at the data quadrature points, i.i.d. uniform[-1,1):
+    array [nrhs][n_cells][n_qp][dim]."""
+    return uniform_pm1(seed, stream, (nrhs, n_cells, n_qp, dim))
+
+
+def trig_coefficients(seed, n_modes=4, stream=0):
+    """Coefficients of phi(x) = sum_{m in {0..n-1}^2, m != 0}
+    a_m cos(pi m.x + theta_m): a_m ~ U[-1,1), theta_m ~ U[0, 2pi).
+    Returns (modes [M,2], a [M], theta [M])."""
+    modes = np.array([(i, j) for j in range(n_modes) for i in range(n_modes)
+                      if (i, j) != (0, 0)], dtype=np.float64)
+    a = uniform_pm1(seed, stream, (len(modes),))
+    theta = 2.0 * np.pi * uniform01(seed, stream + 1, len(modes))
+    return modes, a, theta

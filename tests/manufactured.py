@@ -1,0 +1,41 @@
+"""Manufactured 2D solution of the generalized Stokes problem (Sec. 5.1):
+u = curl(psi) with psi = g(x) g(y), g(t) = t^2 (1-t)^2, so
+u_x = x^2 (x-1)^2 2y(1-y)(2y-1) = -g(x) g'(y), u_y = g'(x) g(y);
+p = x(1-x)(1-y) - 1/12;  f = -nu Lap u + beta u + grad p."""
+import numpy as np
+
+
+def g0(t): return t ** 2 * (1 - t) ** 2
+def g1(t): return 2 * t - 6 * t ** 2 + 4 * t ** 3
+def g2(t): return 2 - 12 * t + 12 * t ** 2
+def g3(t): return -12 + 24 * t
+
+
+def velocity(X):
+    x, y = X[..., 0], X[..., 1]
+    return np.stack([-g0(x) * g1(y), g1(x) * g0(y)], axis=-1)
+
+
+def grad_velocity(X):
+    """[..., i, j] = d u_i / d x_j."""
+    x, y = X[..., 0], X[..., 1]
+    G = np.zeros(X.shape[:-1] + (2, 2))
+    G[..., 0, 0] = -g1(x) * g1(y)
+    G[..., 0, 1] = -g0(x) * g2(y)
+    G[..., 1, 0] = g2(x) * g0(y)
+    G[..., 1, 1] = g1(x) * g1(y)
+    return G
+
+
+def pressure(X):
+    x, y = X[..., 0], X[..., 1]
+    return x * (1 - x) * (1 - y) - 1.0 / 12.0
+
+
+def source(X, nu, beta):
+    x, y = X[..., 0], X[..., 1]
+    lap_ux = -(g2(x) * g1(y) + g0(x) * g3(y))
+    lap_uy = g3(x) * g0(y) + g1(x) * g2(y)
+    u = velocity(X)
+    gp = np.stack([(1 - 2 * x) * (1 - y), -x * (1 - x)], axis=-1)
+    return -nu * np.stack([lap_ux, lap_uy], axis=-1) + beta * u + gp

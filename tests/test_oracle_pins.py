@@ -1,0 +1,348 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test names the passage it checks.  None of them compares the oracle
+with itself: condensed vs fully uncondensed solves, the generic condensation
+vs the closed-form lowest-order operator, the HDG solve vs an independently
+coded CR scheme, exact invariants, convergence rates, and brute force.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import synth
+from oracle import quad, mesh, hdg, cr, mg, krylov, solver
+from tests import manufactured as mf
+
+
+# ----------------------------------------------------------------- inputs
+def test_rng_first_output_is_splitmix64_reference():
+    # splitmix64 from state 0: first output 0xE220A8397B1DCDAF (published
+    # reference sequence of the generator)
+    assert int(synth.splitmix64(0, 0, [0])[0]) == 0xE220A8397B1DCDAF
+
+
+# ------------------------------------------------------------- quadrature
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 6])
+def test_stroud_rule_exact_to_degree_2n_minus_1(n):
+    xi, w = quad.stroud_triangle(n)
+    for a in range(2 * n):
+        for b in range(2 * n - a):
+            exact = math.factorial(a) * math.factorial(b) / math.factorial(a + b + 2)
+            got = 0.5 * np.sum(w * xi[:, 0] ** a * xi[:, 1] ** b)
+            assert abs(got - exact) < 1e-14
+
+
+# ------------------------------------------------------------------- mesh
+def test_red_refinement_of_structured_mesh_is_structured_mesh():
+    c, t = synth.kuhn_square(4)
+    levels = mesh.hierarchy(c, t, 2)
+    c16, t16 = synth.kuhn_square(16)
+    fine = levels[-1]
+    key = lambda C, T: sorted(tuple(sorted(map(tuple, np.round(C[tri], 12)))) for tri in T)
+    assert key(fine.coords, fine.cells) == key(c16, t16)
+    # Appendix-B sizes: 512 cells, 736 interior facets at n = 16
+    assert fine.n_cells == 512 and fine.n_int == 736
+
+
+def test_colouring_is_proper_and_three_colours():
+    c, t = synth.kuhn_square(4)
+    for lv in mesh.hierarchy(c, t, 3):
+        col = lv.vertex_colours()
+        assert np.all(col[lv.edges[:, 0]] != col[lv.edges[:, 1]])
+        assert col.max() == 2
+
+
+def test_facet_orientation_signs_sum_to_zero():
+    c, t = synth.kuhn_square(4)
+    lv = mesh.hierarchy(c, t, 1)[-1]
+    acc = np.zeros(lv.n_facets)
+    for K in range(lv.n_cells):
+        for i in range(3):
+            acc[lv.cell_facets[K, i]] += lv.sigma[K, i]
+    assert np.all(acc[lv.interior] == 0)
+
+
+# --------------------------------------------------------- element (P6)
+@pytest.mark.parametrize("k", [0, 1, 2, 3, 4])
+def test_element_kernel_is_constants_and_mass_exact(k):
+    """beta = 0: the null space of S_K is the traces of constant fields
+    (Lift = 0 for them); beta > 0: <S_K l_c, l_c> = beta |c|^2 |K|."""
+    c, t = synth.kuhn_square(2)
+    lv = mesh.hierarchy(c, t, 1)[-1]
+    K = 5
+    e0 = hdg.Element(lv, K, k, 1.7, 0.0)
+    eb = hdg.Element(lv, K, k, 1.7, 3.0)
+    ev = np.linalg.eigvalsh(e0.S)
+    assert np.sum(np.abs(ev) < 1e-10 * ev.max()) == 2
+    assert np.all(ev > -1e-10 * ev.max())
+    cvec = np.array([0.8, -0.35])
+    lam = np.zeros(6 * (k + 1))
+    for f in range(3):
+        fe = lv.cell_facets[K, f]
+        lam[hdg.lam_index(k, f, 0, 0)] = cvec @ lv.normal[fe]
+        lam[hdg.lam_index(k, f, 1, 0)] = cvec @ lv.tangent[fe]
+    assert np.abs(e0.S @ lam).max() < 1e-11
+    assert abs(lam @ eb.S @ lam - 3.0 * (cvec @ cvec) * lv.area[K]) < 1e-12
+    assert np.all(np.linalg.eigvalsh(eb.S) > 0)
+    assert np.abs(eb.S - eb.S.T).max() < 1e-12 * np.abs(eb.S).max()
+
+
+# ---------------------------------------------------- condensation (P3)
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
+@pytest.mark.parametrize("beta", [0.0, 1.0])
+def test_condensed_equals_uncondensed(k, beta):
+    """The condensed direct solve equals the scheme (stWeak) assembled with
+    no elimination at all (brute force), on a 4x4 mesh."""
+    c, t = synth.kuhn_square(2)
+    lv = mesh.hierarchy(c, t, 1)[-1]
+    f = synth.source_uniform(0, 1, lv.n_cells, (k + 2) ** 2)[0]
+    pr = hdg.Problem(lv, k, 1.0, beta, 1e2)
+    lam, p0 = pr.solve_direct(f)
+    cn, ct, per = hdg.solve_uncondensed(lv, k, 1.0, beta, f)
+    lam_u = np.stack([cn, ct], axis=1).reshape(-1)
+    assert np.abs(lam - lam_u).max() < 1e-10 * np.abs(lam).max()
+    u, p, _, dv = pr.recover(lam, p0, f)
+    for K, (e, a, pc) in enumerate(per):
+        uu = np.einsum("pai,a->pi", e.rt.eval(e.xq)[0], a)
+        pu = e.P.eval(e.xq)[0] @ pc
+        assert np.abs(u[K] - uu).max() < 1e-10 * np.abs(u).max()
+        assert np.abs(p[K] - pu).max() < 1e-9 * np.abs(p).max()
+
+
+# ------------------------------------------------------- lowest order (P1, P2)
+def test_generic_condensation_at_k0_is_closed_form_cr_block():
+    """Thm 3.1 / k0-stOptForm: nu CR stiffness + beta RT0 mass."""
+    c, t = synth.kuhn_square(2)
+    lv = mesh.hierarchy(c, t, 1)[-1]
+    for K in range(lv.n_cells):
+        e = hdg.Element(lv, K, 0, 1.3, 0.7)
+        A = cr.cell_block(lv, K, 1.3, 0.7, 0.0)
+        assert np.abs(e.S - A).max() < 1e-12 * np.abs(A).max()
+
+
+def test_interpolation_identities_lemma_3_2():
+    """Pi^RT Pi^CR v = v and div Pi^CR v = div v (Lemma 3.2), with the RT0
+    field evaluated from its basis functions."""
+    c, t = synth.kuhn_square(2)
+    lv = mesh.hierarchy(c, t, 1)[-1]
+    lam0 = synth.uniform_pm1(5, 0, (2 * lv.n_int,))
+    U = cr.pi_cr(lv, lam0)
+    for K in range(lv.n_cells):
+        vs = np.sort(lv.cells[K])
+        X, _ = quad.data_points(lv.coords[vs], 3)
+        a = cr.rt0_field_from_skeleton(lv, lam0, K, X)
+        b = cr.pi_rt_of_cr(lv, U, K, X)
+        assert np.abs(a - b).max() < 1e-13
+        # divergence: RT0 flux sum vs CR gradient trace
+        fs = lv.cell_facets[K]
+        ids = lv.int_id[fs]
+        div_cr = sum(lv.length[f] * (U[i] @ (lv.sigma[K, j] * lv.normal[f]))
+                     for j, (f, i) in enumerate(zip(fs, ids)) if i >= 0) / lv.area[K]
+        div_rt = sum(lv.sigma[K, j] * lv.length[f] * lam0[2 * i]
+                     for j, (f, i) in enumerate(zip(fs, ids)) if i >= 0) / lv.area[K]
+        assert abs(div_cr - div_rt) < 1e-13
+
+
+@pytest.mark.parametrize("beta", [0.0, 0.7])
+def test_lowest_order_hdg_equals_pressure_robust_cr(beta):
+    """Thm 3.1: Pi^CR u_h = u^CR and p_h = p^CR for the modified CR scheme
+    (equivCRstWeak), solved here in Cartesian midpoint unknowns."""
+    c, t = synth.kuhn_square(4)
+    lv = mesh.hierarchy(c, t, 1)[-1]
+    f = synth.source_uniform(2, 1, lv.n_cells, 4)[0]
+    lam, p0 = hdg.Problem(lv, 0, 1.3, beta, 1.0).solve_direct(f)
+    U, pc = cr.solve_pressure_robust_cr(lv, 1.3, beta, f, 2)
+    assert np.abs(cr.pi_cr(lv, lam) - U).max() < 1e-12 * np.abs(U).max()
+    assert np.abs(p0 - pc).max() < 1e-12 * np.abs(pc).max()
+
+
+# ------------------------------------------------- invariants (P4, P5)
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_velocity_pointwise_divergence_free(k):
+    c, t = synth.kuhn_square(4)
+    lv = mesh.hierarchy(c, t, 1)[-1]
+    f = synth.source_uniform(0, 1, lv.n_cells, (k + 2) ** 2)[0]
+    pr = hdg.Problem(lv, k, 1.0, 1.0, 1e2)
+    lam, p0 = pr.solve_direct(f)
+    u, p, L, dv = pr.recover(lam, p0, f)
+    # |div u_h| against the size of grad u_h (L_h = -nu grad u_h, nu = 1)
+    assert np.abs(dv).max() < 1e-11 * np.abs(L).max()
+
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_pressure_robustness(k):
+    """Adding grad(phi_h), phi_h continuous piecewise linear, to f leaves u_h
+    unchanged and shifts p_h by Pi_k phi_h minus its mean."""
+    c, t = synth.kuhn_square(4)
+    lv = mesh.hierarchy(c, t, 1)[-1]
+    nq = (k + 2) ** 2
+    f = synth.source_uniform(0, 1, lv.n_cells, nq)[0]
+    modes, a, th = synth.trig_coefficients(1)
+    X = lv.coords
+    phi_v = np.sum(a[None, :] * np.cos(np.pi * X @ modes.T + th[None, :]), axis=1)
+    grad = np.zeros((lv.n_cells, 2))
+    phi_q = np.zeros((lv.n_cells, nq))
+    pr = hdg.Problem(lv, k, 1.0, 1.0, 1e2)
+    for K in range(lv.n_cells):
+        V = lv.coords[lv.cells[K]]
+        Mb = np.array([[V[1, 0] - V[0, 0], V[2, 0] - V[0, 0]],
+                       [V[1, 1] - V[0, 1], V[2, 1] - V[0, 1]]])
+        dphi = phi_v[lv.cells[K][1:]] - phi_v[lv.cells[K][0]]
+        grad[K] = np.linalg.solve(Mb.T, dphi)
+        xq = pr.elems[K].xq
+        phi_q[K] = phi_v[lv.cells[K][0]] + (xq - V[0]) @ grad[K]
+    cell_mean = phi_v[lv.cells].mean(axis=1)
+    mean = np.sum(lv.area * cell_mean) / lv.area.sum()
+    f2 = f + grad[:, None, :]
+    lam1, p1 = pr.solve_direct(f)
+    lam2, p2 = pr.solve_direct(f2)
+    assert np.linalg.norm(lam2 - lam1) < 1e-11 * np.linalg.norm(lam1)
+    u1, q1, _, _ = pr.recover(lam1, p1, f)
+    u2, q2, _, _ = pr.recover(lam2, p2, f2)
+    assert np.abs(u2 - u1).max() < 1e-11 * np.abs(u1).max()
+    shift = (phi_q if k >= 1 else cell_mean[:, None]) - mean
+    assert np.abs((q2 - q1) - shift).max() < 1e-10
+
+
+# ------------------------------------------------------------- EOC (P7)
+def _errors(n, k, nu, beta):
+    c, t = synth.kuhn_square(n)
+    lv = mesh.Level(c, t)
+    pr = hdg.Problem(lv, k, nu, beta, 1.0)
+    f = np.array([mf.source(e.xq, nu, beta) for e in pr.elems])
+    lam, p0 = pr.solve_direct(f)
+    eu = eL = ep = 0.0
+    for K, e in enumerate(pr.elems):
+        vs = np.sort(lv.cells[K])
+        X, w = quad.data_points(lv.coords[vs], k + 4)
+        w = w * lv.area[K]
+        u, p, L, _ = e.recover(pr.local(lam, K), p0[K], f[K], X)
+        eu += np.sum(w * np.sum((u - mf.velocity(X)) ** 2, axis=1))
+        eL += np.sum(w * np.sum((L + nu * mf.grad_velocity(X)) ** 2, axis=(1, 2)))
+        ep += np.sum(w * (p - mf.pressure(X)) ** 2)
+    return np.sqrt(eu), np.sqrt(eL), np.sqrt(ep)
+
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+@pytest.mark.parametrize("beta", [0.0, 1.0])
+def test_convergence_orders(k, beta):
+    """Sec. 5.1: optimal order k+1 for u_h and L_h (the EOC tables of the
+    paper are lost; the stated rates remain)."""
+    e = [_errors(n, k, 1.0, beta) for n in (4, 8, 16)]
+    for comp in range(2):
+        rates = [np.log2(e[i][comp] / e[i + 1][comp]) for i in range(2)]
+        assert rates[-1] > k + 1 - 0.25, (comp, rates)
+
+
+def test_manufactured_source_matches_finite_differences():
+    X = np.array([[0.31, 0.62], [0.77, 0.12]])
+    h = 1e-4
+    nu, beta = 1.3, 0.4
+    lap = np.zeros((2, 2))
+    for d in range(2):
+        ed = np.zeros(2)
+        ed[d] = h
+        lap += (mf.velocity(X + ed) - 2 * mf.velocity(X) + mf.velocity(X - ed)) / h ** 2
+    gp = np.stack([(mf.pressure(X + [h, 0]) - mf.pressure(X - [h, 0])) / (2 * h),
+                   (mf.pressure(X + [0, h]) - mf.pressure(X - [0, h])) / (2 * h)], axis=1)
+    ref = -nu * lap + beta * mf.velocity(X) + gp
+    assert np.abs(ref - mf.source(X, nu, beta)).max() < 1e-6
+    # divergence-free and mean-free pressure
+    div = mf.grad_velocity(X)[:, 0, 0] + mf.grad_velocity(X)[:, 1, 1]
+    assert np.abs(div).max() < 1e-14
+
+
+# ----------------------------------------------- Uzawa and MG (P8, P10-P12, P15)
+def _small_setup(k=1, gamma=1e2, beta=1.0, n_refine=1):
+    c, t = synth.kuhn_square(4)
+    return solver.Setup(c, t, n_refine, k, 1.0, beta, gamma)
+
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_preconditioner_symmetric_positive(k):
+    S = _small_setup(k)
+    n = S.Aeps.shape[0]
+    x = synth.uniform_pm1(11, 0, (n,))
+    y = synth.uniform_pm1(12, 0, (n,))
+    Cx, Cy = S.prec(x), S.prec(y)
+    scale = np.linalg.norm(Cx) * np.linalg.norm(y)
+    assert abs(x @ Cy - y @ Cx) < 1e-11 * scale
+    assert x @ Cx > 0 and y @ Cy > 0
+
+
+def test_uzawa_contraction_lemma_3_1():
+    """Pressure error contracts at least like eps/(eps + mu_0), mu_0 the least
+    eigenvalue of B A^-1 B* on mean-free P0 pressures."""
+    c, t = synth.kuhn_square(4)
+    gamma = 3.0
+    S = solver.Setup(c, t, 0, 1, 1.0, 1.0, gamma)
+    A = S.prob.matrix_A().toarray()
+    D = S.D.toarray()
+    W = np.diag(S.lv.area)
+    Schur = D @ np.linalg.solve(A, D.T)
+    # restrict to mean-free pressures: basis orthogonal to |K|
+    w = S.lv.area / np.linalg.norm(S.lv.area)
+    Q = sla.null_space(w[None, :])
+    mu = sla.eigh(Q.T @ Schur @ Q, Q.T @ W @ Q, eigvals_only=True)
+    rate = 1.0 / (1.0 + gamma * mu.min())
+    f = synth.source_uniform(0, 1, S.lv.n_cells, 9)[0]
+    g = S.prob.rhs(f)
+    lam_star, p_star = S.prob.solve_direct(f)
+    Ae = S.Aeps.toarray()
+    p = np.zeros(len(p_star))
+    errs = []
+    for _ in range(4):
+        lam = np.linalg.solve(Ae, g + D.T @ p)
+        p = p - gamma * (D @ lam) / S.lv.area
+        errs.append(np.sqrt(np.sum(S.lv.area * (p - p_star) ** 2)))
+    for a, b in zip(errs, errs[1:]):
+        assert b <= rate * a * (1 + 1e-6)
+
+
+def test_harmonic_transfer_stable_in_gamma():
+    """P12: with the harmonic correction the energy ratio |I v|_A / |v|_A
+    stays bounded as gamma grows; plain averaging does not (Sec. 3.4.2)."""
+    c, t = synth.kuhn_square(4)
+    levels = mesh.hierarchy(c, t, 1)
+    ratios_h, ratios_a = [], []
+    for gamma in (1.0, 1e2, 1e4, 1e6):
+        H = mg.Hierarchy(levels, np.ones(levels[-1].n_cells), 1.0, gamma, harmonic=True)
+        Ac, Af, P = H.A[0].toarray(), H.A[1].toarray(), H.P[1].toarray()
+        ratios_h.append(sla.eigh(P.T @ Af @ P, Ac, eigvals_only=True).max())
+        Ia = mg.averaging(levels[0], levels[1]).toarray()
+        ratios_a.append(sla.eigh(Ia.T @ Af @ Ia, Ac, eigvals_only=True).max())
+    assert max(ratios_h) < 10.0
+    assert ratios_a[-1] > 1e3 * ratios_a[0] or ratios_a[-1] > 1e4
+
+
+def test_multigrid_iterations_flat_in_level_and_gamma():
+    """P11 (soft, Thm 3.2): k = 0 V-cycle PCG counts do not grow with the
+    level or with gamma."""
+    c, t = synth.kuhn_square(2)
+    counts = {}
+    for n_ref in (2, 3, 4):
+        for gamma in (1.0, 1e4):
+            S = solver.Setup(c, t, n_ref, 0, 1.0, 0.0, gamma)
+            b = synth.uniform_pm1(3, 0, (S.Aeps.shape[0],))
+            _, its, _ = S.inner(b)
+            counts[(n_ref, gamma)] = its
+    # bounded, mildly growing counts (the paper's k = 0 column grows
+    # 15/18/19/20 over levels 4..7)
+    assert max(counts.values()) <= 25
+    for gamma in (1.0, 1e4):
+        assert counts[(4, gamma)] - counts[(3, gamma)] <= 3
+        assert counts[(4, gamma)] <= 2 * counts[(4, 1.0)]
+
+
+@pytest.mark.parametrize("k", [0, 2])
+def test_method_reaches_direct_solution(k):
+    """P15: R2 with tight tolerances equals R1."""
+    c, t = synth.kuhn_square(4)
+    S = solver.Setup(c, t, 1, k, 1.0, 1.0, 1e2)
+    f = synth.source_uniform(0, 1, S.lv.n_cells, (k + 2) ** 2)[0]
+    out = S.solve(f, rtol=1e-13, atol=1e-15, uzawa_tol=1e-14)
+    lam, p0 = S.prob.solve_direct(f)
+    assert np.linalg.norm(out["lam"] - lam) < 1e-10 * np.linalg.norm(lam)
+    assert np.abs(out["p0"] - p0).max() < 1e-10 * np.abs(p0).max()
