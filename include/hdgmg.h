@@ -1,0 +1,195 @@
+/*
+ * hdgmg.h -- C ABI of the MI355X (gfx950) library for the hp-multigrid
+ * preconditioned solve of the statically condensed, augmented-Lagrangian
+ * H(div)-HDG skeleton system of the generalized Stokes problem
+ *     -div(nu grad u) + beta u + grad p = f,  div u = 0,  u = 0 on the boundary
+ * (Fu & Kuang, arXiv 2303.06762: Sec. 3.1 model, Sec. 3.2 scheme, Sec. 3.3
+ * augmented-Lagrangian Uzawa iteration, Sec. 3.4-3.5 Alg. 1 / Alg. 2).
+ *
+ * Life cycle: hdgmg_setup -> hdgmg_assemble -> hdgmg_solve (any number of
+ * times) -> hdgmg_destroy.  The operator-level calls (hdgmg_rhs,
+ * hdgmg_apply, hdgmg_precondition, hdgmg_inner_solve, hdgmg_recover) expose
+ * the individual steps of hdgmg_solve on caller-owned device vectors.
+ *
+ * Conventions shared by every call
+ *  - Every function returns hdgmg_status (or a pointer / void where noted);
+ *    none throws, aborts or exits.  A negative status leaves outputs
+ *    undefined; hdgmg_last_error(ctx) describes the failure.
+ *  - "host" pointers are read during the call only.  "device" pointers are
+ *    device (HBM) addresses owned by the caller; they must stay valid until
+ *    the call returns.  All device work is enqueued on the stream given at
+ *    setup; calls return after that stream has been synchronised unless
+ *    stated otherwise.  The library owns the context and its workspace.
+ *  - A context must not be used from two threads at once.
+ *  - Meshes are 2D conforming triangulations.  The coarse mesh is refined
+ *    n_refine times by red refinement (each triangle into four through its
+ *    edge midpoints), giving the nested hierarchy T_1 .. T_J of Sec. 3.4.2,
+ *    J = n_refine + 1.  Numbering of the refined meshes: the midpoint of
+ *    coarse facet e becomes vertex n_vertices + e; coarse cell c = (a,b,c)
+ *    has children 4c+0 = (a,m_ab,m_ca), 4c+1 = (m_ab,b,m_bc),
+ *    4c+2 = (m_ca,m_bc,c), 4c+3 = (m_bc,m_ca,m_ab).  Facets are sorted vertex
+ *    pairs (v0 < v1) numbered lexicographically; interior facets are
+ *    numbered in facet order.
+ *  - Skeleton vectors (length N_skel = 2 (k+1) n_interior_facets, FP64)
+ *    hold, per interior facet F, component c (0: normal trace u.n_F,
+ *    1: tangential trace uhat.t_F, with t_F = (x_v1 - x_v0)/|.|,
+ *    n_F = (t_y, -t_x)) and mode j the coefficient of the orthonormal
+ *    facet Legendre function sqrt(2j+1) P_j(2s-1), s in [0,1] from v0 to v1;
+ *    index (F * 2 + c) * (k+1) + j.
+ *  - Cell data (f, u, p) live at the data quadrature points of each cell:
+ *    the Stroud conical rule with k+2 points per direction (Gauss-Legendre
+ *    in u, Gauss-Jacobi with weight (1-v) in v, point (u(1-v), v), u fastest)
+ *    mapped from the cell's vertices sorted by global index; n_q = (k+2)^2.
+ *    Layouts (C order, FP64): f and u [n_cells][n_q][2]; p [n_cells][n_q].
+ *  - The augmented-Lagrangian weight is eps^-1 = gamma (the paper's
+ *    (nu eps)^-1 with unit reference viscosity).
+ */
+#ifndef HDGMG_H
+#define HDGMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HDGMG_OK = 0,
+  HDGMG_NOT_CONVERGED = 1,  /* outputs hold the last iterate; see info     */
+  HDGMG_EINVAL = -1,        /* bad argument                                 */
+  HDGMG_EMESH = -2,         /* non-conforming / degenerate mesh             */
+  HDGMG_ENOMEM = -3,        /* device or host allocation failed             */
+  HDGMG_EHIP = -4,          /* HIP runtime error                            */
+  HDGMG_ESTATE = -5,        /* call out of order (e.g. solve before assemble) */
+  HDGMG_EBREAKDOWN = -6,    /* Krylov breakdown: p.Ap <= 0 or z.r <= 0      */
+  HDGMG_ENONFINITE = -7     /* NaN/Inf met in the iteration                 */
+} hdgmg_status;
+
+typedef struct hdgmg_ctx hdgmg_ctx;
+
+/* Coarsest mesh T_1 (host arrays, copied during hdgmg_setup). */
+typedef struct {
+  int dim;                 /* must be 2                                    */
+  int n_vertices;
+  const double* coords;    /* host, [n_vertices][2]                        */
+  int n_cells;
+  const int32_t* cells;    /* host, [n_cells][3] vertex indices            */
+  int n_refine;            /* J = n_refine + 1 levels                      */
+} hdgmg_mesh;
+
+/* Solver options (Alg. 1 / Alg. 2 parameters and stopping rules, Sec. 5). */
+typedef struct {
+  int m_relax;             /* m_p: order-k block Gauss-Seidel sweeps       */
+  int m_smooth;            /* m_h: sweeps on the finest lowest-order level */
+  int cycle;               /* q: 1 = V-cycle, 2 = W-cycle (Alg. 1)          */
+  int vcycle_growth;       /* m(l-1) = growth * m(l); 2 = variable V-cycle  */
+  double rtol, atol;       /* inner stop: ||r||_2 <= max(rtol ||r0||_2, atol) */
+  int max_it;              /* inner iteration cap                          */
+  int uzawa_max;           /* AL-Uzawa step cap                            */
+  double uzawa_tol;        /* stop when ||p_n - p_{n-1}||_L2 <= tol*max(1,||p_n||) */
+} hdgmg_opts;
+
+/* Defaults: m_p = m_h = 1, V-cycle, growth 2, rtol 1e-8, atol 1e-10,
+ * max_it 500, uzawa_max 50, uzawa_tol 1e-10. */
+void hdgmg_default_opts(hdgmg_opts* opts);
+
+#define HDGMG_MAX_UZAWA 64
+typedef struct {
+  int uzawa_steps;                 /* Uzawa steps taken                     */
+  int its[HDGMG_MAX_UZAWA];        /* inner iterations per Uzawa step       */
+  double rel_res[HDGMG_MAX_UZAWA]; /* final ||r||/||r0|| per Uzawa step     */
+  double dp_l2[HDGMG_MAX_UZAWA];   /* ||p_n - p_{n-1}||_L2 per step         */
+} hdgmg_info;
+
+/* Build the mesh hierarchy, skeleton topology, vertex patches with their
+ * colouring, and the intergrid transfers; allocate device workspace.
+ *   k      polynomial order, 0 <= k <= 4
+ *   beta   >= 0, the zeroth-order coefficient
+ *   nu     host, nu_len values: 1 (constant viscosity) or the number of
+ *          finest cells (per-cell viscosity); all > 0
+ *   gamma  > 0, eps^-1
+ *   opts   host, may be NULL for the defaults
+ *   stream hipStream_t used for every device operation (NULL: default)
+ * On success *out receives a new context (release with hdgmg_destroy).
+ * Errors: EINVAL (bad k, beta, nu, gamma, opts), EMESH (dim != 2, bad
+ * indices, zero-area cell, facet shared by > 2 cells), ENOMEM, EHIP. */
+hdgmg_status hdgmg_setup(const hdgmg_mesh* mesh, int k, double beta,
+                         const double* nu, int nu_len, double gamma,
+                         const hdgmg_opts* opts, void* stream, hdgmg_ctx** out);
+
+/* Element local solvers and static condensation of the order-k scheme
+ * (stWeak -> stOptForm, with the AL term of stALform), the lowest-order
+ * CR-equivalent operators of every level (k0-stOptForm), the patch block
+ * inverses of every level, the harmonic-extension transfers (div-transfer,
+ * harmonic-ex) and the coarsest-level inverse.  Errors: ESTATE (setup
+ * failed), EHIP, ENONFINITE (a singular local problem). */
+hdgmg_status hdgmg_assemble(hdgmg_ctx* ctx);
+
+/* Full solve (stOpEq-ALU): condensed load from f, AL-Uzawa outer loop with
+ * a flexible-CG inner solve preconditioned by MG_hp (Alg. 2), then local
+ * recovery.
+ *   f_qp   device, [n_cells][n_q][2] source at the data points
+ *   u_qp   device, [n_cells][n_q][2] velocity at the data points (output)
+ *   p_qp   device, [n_cells][n_q] pressure, mean zero (output)
+ *   state  device or NULL, [N_skel + n_cells]: skeleton coefficients then the
+ *          piecewise-constant pressure (output)
+ *   info   host or NULL (output)
+ * Returns OK, NOT_CONVERGED (an inner solve hit max_it or Uzawa hit
+ * uzawa_max; outputs hold the last iterate), ESTATE, EBREAKDOWN, ENONFINITE,
+ * EHIP. */
+hdgmg_status hdgmg_solve(hdgmg_ctx* ctx, const double* f_qp, double* u_qp,
+                         double* p_qp, double* state, hdgmg_info* info);
+
+/* Condensed load g (length N_skel, device, output) of f_qp (device), the
+ * right-hand side F_{k,h} of stOptForm. */
+hdgmg_status hdgmg_rhs(hdgmg_ctx* ctx, const double* f_qp, double* g);
+
+/* y = A^eps_{k,h} x for device skeleton vectors x, y (N_skel). */
+hdgmg_status hdgmg_apply(hdgmg_ctx* ctx, const double* x, double* y);
+
+/* z = MG_hp(r, 0, m_p, m_h, q) (Alg. 2 with zero initial guess) for device
+ * skeleton vectors r, z (N_skel); the preconditioner of the inner solve. */
+hdgmg_status hdgmg_precondition(hdgmg_ctx* ctx, const double* r, double* z);
+
+/* Inner solve A^eps x = b (stOpEq-ALU1) by flexible CG from x = 0,
+ * preconditioned by MG_hp.  b, x device (N_skel).  *its (host) receives the
+ * iteration count and *rel_res (host) the final ||r||/||r0||; either may be
+ * NULL.  Returns OK, NOT_CONVERGED, EBREAKDOWN, ENONFINITE, EHIP. */
+hdgmg_status hdgmg_inner_solve(hdgmg_ctx* ctx, const double* b, double* x,
+                               int* its, double* rel_res);
+
+/* Local recovery (Sec. 3.2): from state [N_skel + n_cells] (device) and
+ * f_qp (device) compute u_qp and p_qp (device) at the data points.  The
+ * pressure is returned as stored (the Uzawa iteration keeps it mean-free). */
+hdgmg_status hdgmg_recover(hdgmg_ctx* ctx, const double* f_qp,
+                           const double* state, double* u_qp, double* p_qp);
+
+/* Sizes.  what: 0 n_cells (finest), 1 n_q, 2 N_skel, 3 levels J,
+ * 4 device bytes held, 5 n_interior_facets (finest), 6 k,
+ * 7 n_colours (finest level), 8 n_cells of level `level`,
+ * 9 N of the lowest-order space of level `level` (2 n_interior_facets).
+ * level counts from 0 (coarsest) and is ignored by 0..7. */
+hdgmg_status hdgmg_query(const hdgmg_ctx* ctx, int what, int level, int64_t* value);
+
+/* Copy an assembled operator to caller memory (device pointer dst, FP64):
+ *   what 0: order-k cell blocks of A^eps [n_cells][6(k+1)][6(k+1)]
+ *   what 1: lowest-order cell blocks of A^eps_{0,l} on level `level`
+ *           [n_cells(level)][6][6]
+ * Local DOF order inside a block: (local facet i, component c, mode j) ->
+ * (i*2 + c)*m + j, local facet i opposite the cell's i-th stored vertex.
+ * `bytes` is the size of dst; EINVAL if too small. */
+hdgmg_status hdgmg_export(const hdgmg_ctx* ctx, int what, int level, void* dst,
+                          size_t bytes);
+
+/* Message of the last failure on ctx (or of the last failed hdgmg_setup when
+ * ctx is NULL).  The pointer stays valid until the next call on ctx. */
+const char* hdgmg_last_error(const hdgmg_ctx* ctx);
+
+/* Release the context and its device memory.  NULL is ignored. */
+void hdgmg_destroy(hdgmg_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,211 @@
+"""Python binding of libhdgmg (include/hdgmg.h): argument marshalling only.
+
+Every step of the solve runs in the HIP library; PyTorch provides device
+memory and the stream.  Importing works without a GPU; creating a Solver
+needs the built library (python -m paper_2303_06762_amd.build) and a GPU,
+and raises otherwise -- there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhdgmg.so")
+_LIB = None
+
+STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "EMESH", -3: "ENOMEM",
+          -4: "EHIP", -5: "ESTATE", -6: "EBREAKDOWN", -7: "ENONFINITE"}
+MAX_UZAWA = 64
+
+
+class Mesh(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n_vertices", ctypes.c_int),
+                ("coords", ctypes.POINTER(ctypes.c_double)), ("n_cells", ctypes.c_int),
+                ("cells", ctypes.POINTER(ctypes.c_int32)), ("n_refine", ctypes.c_int)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("m_relax", ctypes.c_int), ("m_smooth", ctypes.c_int), ("cycle", ctypes.c_int),
+                ("vcycle_growth", ctypes.c_int), ("rtol", ctypes.c_double),
+                ("atol", ctypes.c_double), ("max_it", ctypes.c_int), ("uzawa_max", ctypes.c_int),
+                ("uzawa_tol", ctypes.c_double)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("uzawa_steps", ctypes.c_int), ("its", ctypes.c_int * MAX_UZAWA),
+                ("rel_res", ctypes.c_double * MAX_UZAWA), ("dp_l2", ctypes.c_double * MAX_UZAWA)]
+
+
+class HdgmgError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+SYMBOLS = ["hdgmg_default_opts", "hdgmg_setup", "hdgmg_assemble", "hdgmg_solve", "hdgmg_rhs",
+           "hdgmg_apply", "hdgmg_precondition", "hdgmg_inner_solve", "hdgmg_recover",
+           "hdgmg_query", "hdgmg_export", "hdgmg_last_error", "hdgmg_destroy"]
+
+
+def lib():
+    """Load libhdgmg.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} missing: build it with `python -m paper_2303_06762_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+    L.hdgmg_default_opts.argtypes = [ctypes.POINTER(Opts)]
+    L.hdgmg_default_opts.restype = None
+    L.hdgmg_setup.argtypes = [ctypes.POINTER(Mesh), i32, dbl, ctypes.POINTER(dbl), i32, dbl,
+                              ctypes.POINTER(Opts), vp, ctypes.POINTER(vp)]
+    L.hdgmg_setup.restype = i32
+    L.hdgmg_assemble.argtypes = [vp]
+    L.hdgmg_assemble.restype = i32
+    L.hdgmg_solve.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(Info)]
+    L.hdgmg_solve.restype = i32
+    for name in ("hdgmg_rhs", "hdgmg_apply", "hdgmg_precondition"):
+        getattr(L, name).argtypes = [vp, vp, vp]
+        getattr(L, name).restype = i32
+    L.hdgmg_inner_solve.argtypes = [vp, vp, vp, ctypes.POINTER(i32), ctypes.POINTER(dbl)]
+    L.hdgmg_inner_solve.restype = i32
+    L.hdgmg_recover.argtypes = [vp, vp, vp, vp, vp]
+    L.hdgmg_recover.restype = i32
+    L.hdgmg_query.argtypes = [vp, i32, i32, ctypes.POINTER(i64)]
+    L.hdgmg_query.restype = i32
+    L.hdgmg_export.argtypes = [vp, i32, i32, vp, ctypes.c_size_t]
+    L.hdgmg_export.restype = i32
+    L.hdgmg_last_error.argtypes = [vp]
+    L.hdgmg_last_error.restype = ctypes.c_char_p
+    L.hdgmg_destroy.argtypes = [vp]
+    L.hdgmg_destroy.restype = None
+    _LIB = L
+    return L
+
+
+def default_opts(**kw):
+    o = Opts()
+    lib().hdgmg_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """hdgmg context: setup(mesh hierarchy, k, beta, nu, gamma) -> assemble ->
+    solve(f) -> (u, p).  Tensors are torch float64 CUDA tensors."""
+
+    def __init__(self, coords, cells, n_refine, k, beta, nu, gamma, opts=None, stream=None, **kw):
+        import torch
+        self.torch = torch
+        L = lib()
+        coords = np.ascontiguousarray(coords, dtype=np.float64)
+        cells = np.ascontiguousarray(cells, dtype=np.int32)
+        nu = np.ascontiguousarray(np.atleast_1d(np.asarray(nu, dtype=np.float64)))
+        self._keep = (coords, cells, nu)
+        m = Mesh(2, len(coords), coords.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                 len(cells), cells.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), int(n_refine))
+        if opts is None:
+            opts = default_opts(**kw)
+        self.opts = opts
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = ctypes.c_void_p()
+        st = L.hdgmg_setup(ctypes.byref(m), int(k), float(beta),
+                           nu.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(nu),
+                           float(gamma), ctypes.byref(opts), ctypes.c_void_p(stream.cuda_stream),
+                           ctypes.byref(h))
+        if st != 0:
+            raise HdgmgError(st, L.hdgmg_last_error(None).decode())
+        self._h = h
+        self.k = int(k)
+        self.n_cells = self.query(0)
+        self.n_q = self.query(1)
+        self.n_skel = self.query(2)
+        self.levels = self.query(3)
+
+    def close(self):
+        """Release the context (also done on garbage collection)."""
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _LIB is not None:
+            _LIB.hdgmg_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, allow=(0,)):
+        if st not in allow:
+            raise HdgmgError(st, lib().hdgmg_last_error(self._h).decode())
+        return st
+
+    def _vec(self, n):
+        return self.torch.empty(n, dtype=self.torch.float64, device="cuda")
+
+    def query(self, what, level=0):
+        v = ctypes.c_int64()
+        self._check(lib().hdgmg_query(self._h, what, level, ctypes.byref(v)))
+        return v.value
+
+    def assemble(self):
+        self._check(lib().hdgmg_assemble(self._h))
+
+    def rhs(self, f_qp):
+        g = self._vec(self.n_skel)
+        self._check(lib().hdgmg_rhs(self._h, _ptr(f_qp), _ptr(g)))
+        return g
+
+    def apply(self, x):
+        y = self._vec(self.n_skel)
+        self._check(lib().hdgmg_apply(self._h, _ptr(x), _ptr(y)))
+        return y
+
+    def precondition(self, r):
+        z = self._vec(self.n_skel)
+        self._check(lib().hdgmg_precondition(self._h, _ptr(r), _ptr(z)))
+        return z
+
+    def inner_solve(self, b, x=None):
+        x = self._vec(self.n_skel) if x is None else x
+        its, rel = ctypes.c_int(), ctypes.c_double()
+        st = self._check(lib().hdgmg_inner_solve(self._h, _ptr(b), _ptr(x), ctypes.byref(its),
+                                                 ctypes.byref(rel)), allow=(0, 1))
+        return x, its.value, rel.value, st
+
+    def recover(self, f_qp, state):
+        u = self.torch.empty((self.n_cells, self.n_q, 2), dtype=self.torch.float64, device="cuda")
+        p = self.torch.empty((self.n_cells, self.n_q), dtype=self.torch.float64, device="cuda")
+        self._check(lib().hdgmg_recover(self._h, _ptr(f_qp), _ptr(state), _ptr(u), _ptr(p)))
+        return u, p
+
+    def solve(self, f_qp):
+        """Returns (u_qp, p_qp, state, info dict, status)."""
+        u = self.torch.empty((self.n_cells, self.n_q, 2), dtype=self.torch.float64, device="cuda")
+        p = self.torch.empty((self.n_cells, self.n_q), dtype=self.torch.float64, device="cuda")
+        state = self._vec(self.n_skel + self.n_cells)
+        info = Info()
+        st = self._check(lib().hdgmg_solve(self._h, _ptr(f_qp), _ptr(u), _ptr(p), _ptr(state),
+                                           ctypes.byref(info)), allow=(0, 1))
+        n = info.uzawa_steps
+        d = dict(uzawa_steps=n, its=list(info.its[:n]), rel_res=list(info.rel_res[:n]),
+                 dp_l2=list(info.dp_l2[:n]))
+        return u, p, state, d, st
+
+    def export(self, what, level=0):
+        if what == 0:
+            nK = 6 * (self.k + 1)
+            out = self.torch.empty((self.n_cells, nK, nK), dtype=self.torch.float64, device="cuda")
+        else:
+            out = self.torch.empty((self.query(8, level), 6, 6), dtype=self.torch.float64, device="cuda")
+        self._check(lib().hdgmg_export(self._h, what, level, _ptr(out), out.numel() * 8))
+        return out

@@ -1,0 +1,547 @@
+// Per-cell local solver of the H(div)-HDG scheme and the closed-form
+// lowest-order cell block.  Callable from device kernels (one thread per
+// cell) and from host code (transfer construction).
+//
+// Order-k cell (scheme stWeak, Sec. 3.2).  With Lift(u, uhat) the [P^k]^{2x2}
+// function defined by (Lift, G) = (grad u, G) - <tng(u - uhat), G n_K>, the
+// cell energy is 1/2 [nu |Lift|^2 + beta |u|^2] - (f, u).  For given skeleton
+// data lambda = (c^n, c^t) the interior minimises it over u in RT_k(K) with
+//   N a = c^n          (normal trace moments against the facet Legendre basis)
+//   D a = 0            (div u orthogonal to mean-free P^k: div u in P^0)
+// which is the saddle point
+//   [H_aa N^T D^T] [a]   [F - H_at c^t]
+//   [N    0   0  ] [mu] = [c^n        ]
+//   [D    0   0  ] [pi]   [0          ]      (KKT, pivoted LU).
+// By the envelope theorem the condensed block is
+//   S = blockdiag(0, H_tt) - B^T KKT^-1 B,  B = [[0, -H_at], [I, 0], [0, 0]]
+// (columns c^n, c^t), the load is g = B^T KKT^-1 [F; 0; 0], and the interior
+// pressure is p^o = -sum_r pi_r (q_r - mean q_r)  (stationarity in the
+// interior bubbles).  The AL term eps^-1 |K|^-1 d d^T of stALform is added
+// to S, with d = sigma_{K,F} |F| on each mode-0 normal coefficient.
+//
+// Basis: monomials xi^alpha of the reference coordinates of the affine map
+// from the cell's vertices sorted by global index; RT_k = [P^k]^2 +
+// (x - x_0)/h * {degree-k monomials}.  Quadrature: the data rule (exact to
+// degree 2k+3) and Gauss-Legendre with k+2 points on the facets.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+namespace hdgmg {
+
+#define HDI __host__ __device__ inline
+
+constexpr int KMAX = 4;
+constexpr int NQ_MAX = (KMAX + 2) * (KMAX + 2);
+constexpr int NF_MAX = KMAX + 2;
+
+// Reference quadrature tables, passed to kernels by value.
+struct QuadTables {
+  int k, nq, nfq;
+  double xi[NQ_MAX][2];  // Stroud points on the reference triangle
+  double wq[NQ_MAX];     // weights, sum 1
+  double s[NF_MAX];      // Gauss-Legendre points on [0,1]
+  double ws[NF_MAX];     // weights, sum 1
+};
+
+struct Dims {
+  int k, m, nP, na, nz, nK, nN, nD, nkkt, ntop;
+};
+
+HDI Dims dims_of(int k) {
+  Dims d;
+  d.k = k;
+  d.m = k + 1;
+  d.nP = (k + 1) * (k + 2) / 2;
+  d.ntop = k + 1;
+  d.na = 2 * d.nP + d.ntop;
+  d.nz = d.na + 3 * d.m;
+  d.nK = 6 * d.m;
+  d.nN = 3 * d.m;
+  d.nD = d.nP - 1;
+  d.nkkt = d.na + d.nN + d.nD;
+  return d;
+}
+
+// Strided view into a workspace shared by a batch of cells (one cell per
+// thread, element i of cell t at p[i * s + t]): coalesced across a wavefront.
+struct WS {
+  double* p;
+  long s;
+  HDI double& operator[](long i) const { return p[i * s]; }
+};
+
+// Monomials xi1^a xi2^b, ordered by degree d then by b = 0..d; values and
+// reference derivatives.
+HDI void monomials(int k, double x1, double x2, double* v, double* d1, double* d2) {
+  double p1[KMAX + 2], p2[KMAX + 2];
+  p1[0] = p2[0] = 1.0;
+  for (int i = 1; i <= k; ++i) {
+    p1[i] = p1[i - 1] * x1;
+    p2[i] = p2[i - 1] * x2;
+  }
+  int r = 0;
+  for (int d = 0; d <= k; ++d)
+    for (int b = 0; b <= d; ++b, ++r) {
+      int a = d - b;
+      v[r] = p1[a] * p2[b];
+      d1[r] = a > 0 ? a * p1[a - 1] * p2[b] : 0.0;
+      d2[r] = b > 0 ? b * p1[a] * p2[b - 1] : 0.0;
+    }
+}
+
+// Orthonormal facet functions sqrt(2j+1) P_j(2s-1), j = 0..k.
+HDI void facet_legendre(int k, double s, double* phi) {
+  double t = 2.0 * s - 1.0;
+  double pm = 1.0, p = t;
+  phi[0] = 1.0;
+  if (k >= 1) phi[1] = sqrt(3.0) * t;
+  for (int j = 2; j <= k; ++j) {
+    double pn = ((2 * j - 1) * t * p - (j - 1) * pm) / j;
+    pm = p;
+    p = pn;
+    phi[j] = sqrt(2.0 * j + 1.0) * pn;
+  }
+}
+
+// Geometry of one cell.
+struct CellGeom {
+  double X[3][2];     // stored vertex order
+  int vid[3];
+  double Xs0[2];      // sorted-vertex map x = Xs0 + J xi
+  double J[2][2], Ji[2][2];
+  double area, h;
+  // local facet i (opposite stored vertex i)
+  double P0[3][2], P1[3][2];  // endpoints in global order (v0 < v1)
+  double t[3][2], n[3][2], len[3];
+  int sigma[3];
+};
+
+HDI void cell_geom(const double* Xall, const int* cell, CellGeom& g) {
+  for (int i = 0; i < 3; ++i) {
+    g.vid[i] = cell[i];
+    g.X[i][0] = Xall[2 * cell[i]];
+    g.X[i][1] = Xall[2 * cell[i] + 1];
+  }
+  int o[3] = {0, 1, 2};
+  for (int a = 0; a < 3; ++a)
+    for (int b = a + 1; b < 3; ++b)
+      if (g.vid[o[b]] < g.vid[o[a]]) {
+        int t = o[a];
+        o[a] = o[b];
+        o[b] = t;
+      }
+  g.Xs0[0] = g.X[o[0]][0];
+  g.Xs0[1] = g.X[o[0]][1];
+  for (int r = 0; r < 2; ++r) {
+    g.J[r][0] = g.X[o[1]][r] - g.Xs0[r];
+    g.J[r][1] = g.X[o[2]][r] - g.Xs0[r];
+  }
+  double det = g.J[0][0] * g.J[1][1] - g.J[0][1] * g.J[1][0];
+  g.Ji[0][0] = g.J[1][1] / det;
+  g.Ji[0][1] = -g.J[0][1] / det;
+  g.Ji[1][0] = -g.J[1][0] / det;
+  g.Ji[1][1] = g.J[0][0] / det;
+  g.area = 0.5 * fabs(det);
+  g.h = sqrt(2.0 * g.area);
+  for (int i = 0; i < 3; ++i) {
+    int a = (i + 1) % 3, b = (i + 2) % 3;
+    if (g.vid[b] < g.vid[a]) {
+      int t = a;
+      a = b;
+      b = t;
+    }
+    double dx = g.X[b][0] - g.X[a][0], dy = g.X[b][1] - g.X[a][1];
+    double l = sqrt(dx * dx + dy * dy);
+    g.len[i] = l;
+    g.P0[i][0] = g.X[a][0];
+    g.P0[i][1] = g.X[a][1];
+    g.P1[i][0] = g.X[b][0];
+    g.P1[i][1] = g.X[b][1];
+    g.t[i][0] = dx / l;
+    g.t[i][1] = dy / l;
+    g.n[i][0] = dy / l;
+    g.n[i][1] = -dx / l;
+    double mx = 0.5 * (g.X[a][0] + g.X[b][0]) - g.X[i][0];
+    double my = 0.5 * (g.X[a][1] + g.X[b][1]) - g.X[i][1];
+    g.sigma[i] = (mx * g.n[i][0] + my * g.n[i][1]) > 0 ? 1 : -1;
+  }
+}
+
+// RT_k basis at a point: values u[a][i], gradients gr[a][i][j] = du_i/dx_j.
+HDI void rt_basis(const Dims& D, const CellGeom& g, double x1, double x2, const double* xphys,
+                  double* u, double* gr, double* mono) {
+  double v[16], d1[16], d2[16];
+  monomials(D.k, x1, x2, v, d1, d2);
+  for (int r = 0; r < D.nP; ++r) mono[r] = v[r];
+  for (int r = 0; r < D.nP; ++r) {
+    double gx = d1[r] * g.Ji[0][0] + d2[r] * g.Ji[1][0];
+    double gy = d1[r] * g.Ji[0][1] + d2[r] * g.Ji[1][1];
+    int a0 = 2 * r, a1 = 2 * r + 1;
+    u[2 * a0] = v[r];
+    u[2 * a0 + 1] = 0.0;
+    u[2 * a1] = 0.0;
+    u[2 * a1 + 1] = v[r];
+    gr[4 * a0 + 0] = gx;
+    gr[4 * a0 + 1] = gy;
+    gr[4 * a0 + 2] = 0.0;
+    gr[4 * a0 + 3] = 0.0;
+    gr[4 * a1 + 0] = 0.0;
+    gr[4 * a1 + 1] = 0.0;
+    gr[4 * a1 + 2] = gx;
+    gr[4 * a1 + 3] = gy;
+  }
+  double y0 = (xphys[0] - g.Xs0[0]) / g.h, y1 = (xphys[1] - g.Xs0[1]) / g.h;
+  for (int t = 0; t < D.ntop; ++t) {
+    int r = D.nP - D.ntop + t;
+    int a = 2 * D.nP + t;
+    double gx = d1[r] * g.Ji[0][0] + d2[r] * g.Ji[1][0];
+    double gy = d1[r] * g.Ji[0][1] + d2[r] * g.Ji[1][1];
+    u[2 * a] = y0 * v[r];
+    u[2 * a + 1] = y1 * v[r];
+    gr[4 * a + 0] = v[r] / g.h + y0 * gx;
+    gr[4 * a + 1] = y0 * gy;
+    gr[4 * a + 2] = y1 * gx;
+    gr[4 * a + 3] = v[r] / g.h + y1 * gy;
+  }
+}
+
+// Workspace size (doubles per cell) for order k.
+HDI long element_ws_size(int k) {
+  Dims D = dims_of(k);
+  long n = 0;
+  n += D.nP * D.nP;             // M
+  n += 4L * D.nP * D.nz;        // R
+  n += (long)D.nP * D.nz;       // Y
+  n += (long)D.nz * D.nz;       // H
+  n += (long)D.nN * D.na;       // N
+  n += (long)D.nP * D.na;       // Dr
+  n += D.na;                    // F
+  n += (long)D.nkkt * D.nkkt;   // KKT
+  n += D.nkkt;                  // pivots
+  n += (long)D.nkkt * D.nK;     // right-hand sides / solutions
+  n += D.nP;                    // means
+  return n;
+}
+
+enum { EL_CONDENSE = 0, EL_LOAD = 1, EL_RECOVER = 2 };
+
+// The local solve of one cell.  Returns 0 on success, 1 if the KKT matrix
+// is singular.  Inputs/outputs by mode:
+//   EL_CONDENSE: out = S^eps [nK][nK] (row-major)
+//   EL_LOAD:     f [nq][2] at the data points; out = g [nK]
+//   EL_RECOVER:  f, lam [nK], p0; out = u [nq][2] then p [nq]
+HDI int element_local(const QuadTables& Q, const CellGeom& g, double nu, double beta,
+                      double eps_inv, int mode, const double* f, const double* lam,
+                      double p0, WS w, double* out) {
+  const Dims D = dims_of(Q.k);
+  const int nP = D.nP, na = D.na, nz = D.nz, m = D.m, nK = D.nK, nN = D.nN, nkkt = D.nkkt;
+  long o = 0;
+  WS M{w.p + o * w.s, w.s};
+  o += nP * nP;
+  WS R{w.p + o * w.s, w.s};
+  o += 4L * nP * nz;
+  WS Y{w.p + o * w.s, w.s};
+  o += (long)nP * nz;
+  WS H{w.p + o * w.s, w.s};
+  o += (long)nz * nz;
+  WS Nm{w.p + o * w.s, w.s};
+  o += (long)nN * na;
+  WS Dr{w.p + o * w.s, w.s};
+  o += (long)nP * na;
+  WS F{w.p + o * w.s, w.s};
+  o += na;
+  WS Kk{w.p + o * w.s, w.s};
+  o += (long)nkkt * nkkt;
+  WS piv{w.p + o * w.s, w.s};
+  o += nkkt;
+  WS Bx{w.p + o * w.s, w.s};
+  o += (long)nkkt * nK;
+  WS mean{w.p + o * w.s, w.s};
+
+  for (long i = 0; i < (long)nP * nP; ++i) M[i] = 0.0;
+  for (long i = 0; i < 4L * nP * nz; ++i) R[i] = 0.0;
+  for (long i = 0; i < (long)nz * nz; ++i) H[i] = 0.0;
+  for (long i = 0; i < (long)nN * na; ++i) Nm[i] = 0.0;
+  for (long i = 0; i < (long)nP * na; ++i) Dr[i] = 0.0;
+  for (int i = 0; i < na; ++i) F[i] = 0.0;
+  for (int i = 0; i < nP; ++i) mean[i] = 0.0;
+
+  double u[2 * 40], gr[4 * 40], mono[16];
+  // ---- volume terms
+  for (int q = 0; q < Q.nq; ++q) {
+    double x1 = Q.xi[q][0], x2 = Q.xi[q][1];
+    double xp[2] = {g.Xs0[0] + g.J[0][0] * x1 + g.J[0][1] * x2,
+                    g.Xs0[1] + g.J[1][0] * x1 + g.J[1][1] * x2};
+    double wt = Q.wq[q] * g.area;
+    rt_basis(D, g, x1, x2, xp, u, gr, mono);
+    for (int r = 0; r < nP; ++r) {
+      mean[r] += wt * mono[r];
+      for (int s = 0; s < nP; ++s) M[r * nP + s] += wt * mono[r] * mono[s];
+    }
+    for (int a = 0; a < na; ++a) {
+      double dv = gr[4 * a + 0] + gr[4 * a + 3];
+      for (int r = 0; r < nP; ++r) {
+        double wm = wt * mono[r];
+        for (int ij = 0; ij < 4; ++ij) R[((long)ij * nP + r) * nz + a] += wm * gr[4 * a + ij];
+        Dr[(long)r * na + a] += wm * dv;
+      }
+      for (int b = 0; b <= a; ++b)
+        H[(long)a * nz + b] += beta * wt * (u[2 * a] * u[2 * b] + u[2 * a + 1] * u[2 * b + 1]);
+      if (mode != EL_CONDENSE) F[a] += wt * (f[2 * q] * u[2 * a] + f[2 * q + 1] * u[2 * a + 1]);
+    }
+  }
+  for (int a = 0; a < na; ++a)
+    for (int b = 0; b < a; ++b) H[(long)b * nz + a] = H[(long)a * nz + b];
+  for (int r = 0; r < nP; ++r) mean[r] /= g.area;
+  // ---- facet terms
+  double phi[KMAX + 1];
+  for (int i = 0; i < 3; ++i) {
+    const double* t = g.t[i];
+    double nK_[2] = {g.sigma[i] * g.n[i][0], g.sigma[i] * g.n[i][1]};
+    for (int l = 0; l < Q.nfq; ++l) {
+      double s = Q.s[l];
+      double xp[2] = {g.P0[i][0] + s * (g.P1[i][0] - g.P0[i][0]),
+                      g.P0[i][1] + s * (g.P1[i][1] - g.P0[i][1])};
+      double dx = xp[0] - g.Xs0[0], dy = xp[1] - g.Xs0[1];
+      double x1 = g.Ji[0][0] * dx + g.Ji[0][1] * dy;
+      double x2 = g.Ji[1][0] * dx + g.Ji[1][1] * dy;
+      rt_basis(D, g, x1, x2, xp, u, gr, mono);
+      facet_legendre(D.k, s, phi);
+      double wl = Q.ws[l] * g.len[i];
+      for (int r = 0; r < nP; ++r) {
+        for (int ii = 0; ii < 2; ++ii)
+          for (int jj = 0; jj < 2; ++jj) {
+            double c = wl * mono[r] * t[ii] * nK_[jj];
+            long row = ((long)(ii * 2 + jj) * nP + r) * nz;
+            for (int a = 0; a < na; ++a) R[row + a] -= c * (u[2 * a] * t[0] + u[2 * a + 1] * t[1]);
+            for (int j = 0; j < m; ++j) R[row + na + i * m + j] += c * phi[j];
+          }
+      }
+      for (int j = 0; j < m; ++j)
+        for (int a = 0; a < na; ++a)
+          Nm[(long)(i * m + j) * na + a] +=
+              Q.ws[l] * phi[j] * (u[2 * a] * g.n[i][0] + u[2 * a + 1] * g.n[i][1]);
+    }
+  }
+  // ---- H += nu sum_ij R_ij^T M^-1 R_ij (Cholesky of M)
+  for (int j = 0; j < nP; ++j) {
+    double d = M[j * nP + j];
+    for (int p = 0; p < j; ++p) d -= M[j * nP + p] * M[j * nP + p];
+    if (!(d > 0)) return 1;
+    d = sqrt(d);
+    M[j * nP + j] = d;
+    for (int i = j + 1; i < nP; ++i) {
+      double s = M[i * nP + j];
+      for (int p = 0; p < j; ++p) s -= M[i * nP + p] * M[j * nP + p];
+      M[i * nP + j] = s / d;
+    }
+  }
+  for (int ij = 0; ij < 4; ++ij) {
+    // Y = L^-1 R_ij, then H += nu Y^T Y
+    for (int c = 0; c < nz; ++c)
+      for (int r = 0; r < nP; ++r) {
+        double s = R[((long)ij * nP + r) * nz + c];
+        for (int p = 0; p < r; ++p) s -= M[r * nP + p] * Y[(long)p * nz + c];
+        Y[(long)r * nz + c] = s / M[r * nP + r];
+      }
+    for (int a = 0; a < nz; ++a)
+      for (int b = 0; b <= a; ++b) {
+        double s = 0.0;
+        for (int r = 0; r < nP; ++r) s += Y[(long)r * nz + a] * Y[(long)r * nz + b];
+        H[(long)a * nz + b] += nu * s;
+        if (b != a) H[(long)b * nz + a] += nu * s;
+      }
+  }
+  // ---- KKT matrix
+  for (long i = 0; i < (long)nkkt * nkkt; ++i) Kk[i] = 0.0;
+  for (int a = 0; a < na; ++a)
+    for (int b = 0; b < na; ++b) Kk[(long)a * nkkt + b] = H[(long)a * nz + b];
+  for (int c = 0; c < nN; ++c)
+    for (int a = 0; a < na; ++a) {
+      Kk[(long)(na + c) * nkkt + a] = Nm[(long)c * na + a];
+      Kk[(long)a * nkkt + na + c] = Nm[(long)c * na + a];
+    }
+  for (int r = 1; r < nP; ++r)
+    for (int a = 0; a < na; ++a) {
+      double dval = Dr[(long)r * na + a] - mean[r] * Dr[a];
+      Kk[(long)(na + nN + r - 1) * nkkt + a] = dval;
+      Kk[(long)a * nkkt + na + nN + r - 1] = dval;
+    }
+  // ---- LU with partial pivoting
+  for (int j = 0; j < nkkt; ++j) {
+    int pr = j;
+    double best = fabs(Kk[(long)j * nkkt + j]);
+    for (int i = j + 1; i < nkkt; ++i) {
+      double v = fabs(Kk[(long)i * nkkt + j]);
+      if (v > best) {
+        best = v;
+        pr = i;
+      }
+    }
+    if (!(best > 0)) return 1;
+    piv[j] = (double)pr;
+    if (pr != j)
+      for (int c = 0; c < nkkt; ++c) {
+        double t = Kk[(long)j * nkkt + c];
+        Kk[(long)j * nkkt + c] = Kk[(long)pr * nkkt + c];
+        Kk[(long)pr * nkkt + c] = t;
+      }
+    double dj = Kk[(long)j * nkkt + j];
+    for (int i = j + 1; i < nkkt; ++i) {
+      double l = Kk[(long)i * nkkt + j] / dj;
+      Kk[(long)i * nkkt + j] = l;
+      if (l != 0.0)
+        for (int c = j + 1; c < nkkt; ++c) Kk[(long)i * nkkt + c] -= l * Kk[(long)j * nkkt + c];
+    }
+  }
+  // ---- right-hand sides
+  int ncol = mode == EL_CONDENSE ? nK : 1;
+  for (long i = 0; i < (long)nkkt * ncol; ++i) Bx[i] = 0.0;
+  if (mode == EL_CONDENSE) {
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < m; ++j) {
+        int ln = (i * 2 + 0) * m + j, lt = (i * 2 + 1) * m + j;
+        Bx[(long)(na + i * m + j) * ncol + ln] = 1.0;
+        for (int a = 0; a < na; ++a) Bx[(long)a * ncol + lt] = -H[(long)a * nz + na + i * m + j];
+      }
+  } else {
+    for (int a = 0; a < na; ++a) Bx[(long)a * ncol] = F[a];
+    if (mode == EL_RECOVER) {
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < m; ++j) {
+          double cn = lam[(i * 2 + 0) * m + j], ct = lam[(i * 2 + 1) * m + j];
+          Bx[(long)(na + i * m + j) * ncol] += cn;
+          for (int a = 0; a < na; ++a) Bx[(long)a * ncol] -= H[(long)a * nz + na + i * m + j] * ct;
+        }
+    }
+  }
+  // apply the row permutation, then forward / backward substitution
+  for (int j = 0; j < nkkt; ++j) {
+    int pr = (int)piv[j];
+    if (pr != j)
+      for (int c = 0; c < ncol; ++c) {
+        double t = Bx[(long)j * ncol + c];
+        Bx[(long)j * ncol + c] = Bx[(long)pr * ncol + c];
+        Bx[(long)pr * ncol + c] = t;
+      }
+  }
+  for (int c = 0; c < ncol; ++c) {
+    for (int i = 0; i < nkkt; ++i) {
+      double s = Bx[(long)i * ncol + c];
+      for (int p = 0; p < i; ++p) s -= Kk[(long)i * nkkt + p] * Bx[(long)p * ncol + c];
+      Bx[(long)i * ncol + c] = s;
+    }
+    for (int i = nkkt - 1; i >= 0; --i) {
+      double s = Bx[(long)i * ncol + c];
+      for (int p = i + 1; p < nkkt; ++p) s -= Kk[(long)i * nkkt + p] * Bx[(long)p * ncol + c];
+      Bx[(long)i * ncol + c] = s / Kk[(long)i * nkkt + i];
+    }
+  }
+  // ---- outputs
+  if (mode == EL_CONDENSE || mode == EL_LOAD) {
+    // rows of B^T X: normal (i,0,j) -> X[na + i m + j]; tangential (i,1,j) ->
+    // -sum_a H[a][na + i m + j] X[a]
+    for (int l1 = 0; l1 < nK; ++l1) {
+      int i = l1 / (2 * m), c = (l1 / m) % 2, j = l1 % m;
+      for (int cc = 0; cc < ncol; ++cc) {
+        double btx;
+        if (c == 0) {
+          btx = Bx[(long)(na + i * m + j) * ncol + cc];
+        } else {
+          btx = 0.0;
+          for (int a = 0; a < na; ++a) btx -= H[(long)a * nz + na + i * m + j] * Bx[(long)a * ncol + cc];
+        }
+        if (mode == EL_LOAD) {
+          out[l1] = btx;
+        } else {
+          int l2 = cc;
+          int i2 = l2 / (2 * m), c2 = (l2 / m) % 2, j2 = l2 % m;
+          double htt = (c == 1 && c2 == 1) ? H[(long)(na + i * m + j) * nz + na + i2 * m + j2] : 0.0;
+          out[l1 * nK + l2] = htt - btx;
+        }
+      }
+    }
+    if (mode == EL_CONDENSE) {
+      for (int a = 0; a < nK; ++a)
+        for (int b = 0; b < a; ++b) {
+          double s = 0.5 * (out[a * nK + b] + out[b * nK + a]);
+          out[a * nK + b] = s;
+          out[b * nK + a] = s;
+        }
+      for (int i1 = 0; i1 < 3; ++i1)
+        for (int i2 = 0; i2 < 3; ++i2)
+          out[(i1 * 2 * m) * nK + i2 * 2 * m] +=
+              eps_inv / g.area * (g.sigma[i1] * g.len[i1]) * (g.sigma[i2] * g.len[i2]);
+    }
+  } else {
+    // recovery at the data points
+    for (int q = 0; q < Q.nq; ++q) {
+      double x1 = Q.xi[q][0], x2 = Q.xi[q][1];
+      double xp[2] = {g.Xs0[0] + g.J[0][0] * x1 + g.J[0][1] * x2,
+                      g.Xs0[1] + g.J[1][0] * x1 + g.J[1][1] * x2};
+      rt_basis(D, g, x1, x2, xp, u, gr, mono);
+      double ux = 0.0, uy = 0.0;
+      for (int a = 0; a < na; ++a) {
+        ux += Bx[a] * u[2 * a];
+        uy += Bx[a] * u[2 * a + 1];
+      }
+      double p = p0;
+      for (int r = 1; r < nP; ++r) p -= Bx[na + nN + r - 1] * (mono[r] - mean[r]);
+      out[2 * q] = ux;
+      out[2 * q + 1] = uy;
+      out[2 * Q.nq + q] = p;
+    }
+  }
+  return 0;
+}
+
+// Closed-form lowest-order cell block of A^eps_{0,h} (k0-stOptForm) on the
+// local DOFs (facet i, component c) -> 2i + c:
+//   nu (grad Pi^CR u, grad Pi^CR v) + beta (u_RT0, v_RT0) + eps^-1 (div u, div v)
+// CR basis gradient of facet i: |F_i| n_{K,i} / |K|; the RT0 basis with unit
+// outward flux through facet i is (x - x_i) / (2|K|), whose products
+// integrate exactly by int_K f g = |K|/12 [sum f_m . sum g_m + sum f_m . g_m]
+// over vertex values of affine f, g.
+HDI void cr_block(const CellGeom& g, double nu, double beta, double eps_inv, double* A) {
+  double e[3][2][2];  // frame vectors (n, t) of each local facet
+  double gradphi[3][2];
+  double q[3];
+  for (int i = 0; i < 3; ++i) {
+    e[i][0][0] = g.n[i][0];
+    e[i][0][1] = g.n[i][1];
+    e[i][1][0] = g.t[i][0];
+    e[i][1][1] = g.t[i][1];
+    gradphi[i][0] = g.len[i] * g.sigma[i] * g.n[i][0] / g.area;
+    gradphi[i][1] = g.len[i] * g.sigma[i] * g.n[i][1] / g.area;
+    q[i] = g.sigma[i] * g.len[i];
+  }
+  double Mrt[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double si[2] = {0, 0}, sj[2] = {0, 0}, sd = 0.0;
+      for (int mm = 0; mm < 3; ++mm) {
+        double fi0 = g.X[mm][0] - g.X[i][0], fi1 = g.X[mm][1] - g.X[i][1];
+        double fj0 = g.X[mm][0] - g.X[j][0], fj1 = g.X[mm][1] - g.X[j][1];
+        si[0] += fi0;
+        si[1] += fi1;
+        sj[0] += fj0;
+        sj[1] += fj1;
+        sd += fi0 * fj0 + fi1 * fj1;
+      }
+      Mrt[i][j] = g.area / 12.0 * (si[0] * sj[0] + si[1] * sj[1] + sd) / (4.0 * g.area * g.area);
+    }
+  for (int i = 0; i < 3; ++i)
+    for (int a = 0; a < 2; ++a)
+      for (int j = 0; j < 3; ++j)
+        for (int b = 0; b < 2; ++b) {
+          double ee = e[i][a][0] * e[j][b][0] + e[i][a][1] * e[j][b][1];
+          double gg = gradphi[i][0] * gradphi[j][0] + gradphi[i][1] * gradphi[j][1];
+          double v = nu * ee * gg * g.area;
+          if (a == 0 && b == 0) v += beta * q[i] * q[j] * Mrt[i][j] + eps_inv * q[i] * q[j] / g.area;
+          A[(2 * i + a) * 6 + 2 * j + b] = v;
+        }
+}
+
+}  // namespace hdgmg

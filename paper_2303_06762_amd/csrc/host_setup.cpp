@@ -1,0 +1,296 @@
+// Host-side numeric setup (quadrature tables, transfers, coarsest inverse).
+#include "host_setup.hpp"
+
+#include <cmath>
+#include <cstring>
+#include <map>
+
+namespace hdgmg {
+
+namespace {
+// Gauss-Legendre on [0,1] (ascending nodes, weights sum 1) by Newton on P_n.
+void gauss_legendre01(int n, double* x, double* w) {
+  for (int i = 0; i < n; ++i) {
+    double t = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    double p0 = 1.0, p1 = t, dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      p0 = 1.0;
+      p1 = t;
+      for (int j = 2; j <= n; ++j) {
+        double p2 = ((2 * j - 1) * t * p1 - (j - 1) * p0) / j;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (t * p1 - p0) / (t * t - 1.0);
+      double dt = p1 / dp;
+      t -= dt;
+      if (std::fabs(dt) < 1e-16) break;
+    }
+    p0 = 1.0;
+    p1 = t;
+    for (int j = 2; j <= n; ++j) {
+      double p2 = ((2 * j - 1) * t * p1 - (j - 1) * p0) / j;
+      p0 = p1;
+      p1 = p2;
+    }
+    dp = n * (t * p1 - p0) / (t * t - 1.0);
+    x[n - 1 - i] = 0.5 * (t + 1.0);              // cos ordering is descending
+    w[n - 1 - i] = 1.0 / ((1.0 - t * t) * dp * dp);  // (2 / ((1-t^2) P_n'^2)) / 2
+  }
+}
+
+// Jacobi P_n^{(1,0)} and its derivative.
+void jacobi10(int n, double t, double& pn, double& dpn) {
+  const double a = 1.0, b = 0.0;
+  double p0 = 1.0, p1 = (a + 1.0) + (a + b + 2.0) * (t - 1.0) / 2.0;
+  if (n == 0) {
+    pn = 1.0;
+    dpn = 0.0;
+    return;
+  }
+  for (int j = 2; j <= n; ++j) {
+    double c1 = 2.0 * j * (j + a + b) * (2.0 * j + a + b - 2.0);
+    double c2 = (2.0 * j + a + b - 1.0) * ((2.0 * j + a + b) * (2.0 * j + a + b - 2.0) * t + a * a - b * b);
+    double c3 = 2.0 * (j + a - 1.0) * (j + b - 1.0) * (2.0 * j + a + b);
+    double p2 = (c2 * p1 - c3 * p0) / c1;
+    p0 = p1;
+    p1 = p2;
+  }
+  pn = p1;
+  // (2n+a+b)(1-t^2) P_n' = n[(a-b) - (2n+a+b) t] P_n + 2(n+a)(n+b) P_{n-1}
+  dpn = (n * ((a - b) - (2.0 * n + a + b) * t) * p1 + 2.0 * (n + a) * (n + b) * p0) /
+        ((2.0 * n + a + b) * (1.0 - t * t));
+}
+
+// Gauss-Jacobi nodes/weights for int_0^1 (1-v) g(v) dv: roots of
+// P_n^{(1,0)} bracketed on a grid, refined by bisection then Newton.
+void gauss_jacobi10_01(int n, double* x, double* w) {
+  const int G = 4000;
+  int found = 0;
+  double prev_t = -1.0 + 1e-12, pv, dv;
+  jacobi10(n, prev_t, pv, dv);
+  for (int i = 1; i <= G && found < n; ++i) {
+    double t = -1.0 + 2.0 * i / G;
+    if (i == G) t = 1.0 - 1e-12;
+    double pc, dc;
+    jacobi10(n, t, pc, dc);
+    if ((pv < 0) != (pc < 0)) {
+      double lo = prev_t, hi = t, plo = pv;
+      for (int it = 0; it < 60; ++it) {
+        double mid = 0.5 * (lo + hi), pm, dm;
+        jacobi10(n, mid, pm, dm);
+        if ((pm < 0) == (plo < 0)) {
+          lo = mid;
+          plo = pm;
+        } else {
+          hi = mid;
+        }
+      }
+      double r = 0.5 * (lo + hi);
+      for (int it = 0; it < 5; ++it) {
+        double pr, dr;
+        jacobi10(n, r, pr, dr);
+        if (dr == 0) break;
+        r -= pr / dr;
+      }
+      double pr, dr;
+      jacobi10(n, r, pr, dr);
+      x[found] = 0.5 * (r + 1.0);
+      w[found] = (4.0 / ((1.0 - r * r) * dr * dr)) / 4.0;
+      ++found;
+    }
+    prev_t = t;
+    pv = pc;
+  }
+}
+
+}  // namespace
+
+QuadTables make_tables(int k) {
+  QuadTables Q;
+  std::memset(&Q, 0, sizeof(Q));
+  Q.k = k;
+  const int n = k + 2;
+  Q.nq = n * n;
+  Q.nfq = n;
+  double u[NF_MAX], wu[NF_MAX], v[NF_MAX], wv[NF_MAX];
+  gauss_legendre01(n, u, wu);
+  gauss_jacobi10_01(n, v, wv);
+  double tot = 0.0;
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) {
+      int q = j * n + i;
+      Q.xi[q][0] = u[i] * (1.0 - v[j]);
+      Q.xi[q][1] = v[j];
+      Q.wq[q] = wu[i] * wv[j];
+      tot += Q.wq[q];
+    }
+  for (int q = 0; q < Q.nq; ++q) Q.wq[q] /= tot;
+  for (int i = 0; i < n; ++i) {
+    Q.s[i] = u[i];
+    Q.ws[i] = wu[i];
+  }
+  return Q;
+}
+
+// ------------------------------------------------------------ dense helpers
+bool invert_spd(const std::vector<double>& A, int n, std::vector<double>& inv) {
+  // Cholesky then column solves; inv column-major (symmetric anyway)
+  std::vector<double> L(A);
+  for (int j = 0; j < n; ++j) {
+    double d = L[(size_t)j * n + j];
+    for (int q = 0; q < j; ++q) d -= L[(size_t)j * n + q] * L[(size_t)j * n + q];
+    if (!(d > 0)) return false;
+    d = std::sqrt(d);
+    L[(size_t)j * n + j] = d;
+    for (int i = j + 1; i < n; ++i) {
+      double s = L[(size_t)i * n + j];
+      for (int q = 0; q < j; ++q) s -= L[(size_t)i * n + q] * L[(size_t)j * n + q];
+      L[(size_t)i * n + j] = s / d;
+    }
+  }
+  inv.assign((size_t)n * n, 0.0);
+  std::vector<double> col(n);
+  for (int c = 0; c < n; ++c) {
+    for (int i = 0; i < n; ++i) {
+      double s = i == c ? 1.0 : 0.0;
+      for (int q = 0; q < i; ++q) s -= L[(size_t)i * n + q] * col[q];
+      col[i] = s / L[(size_t)i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double s = col[i];
+      for (int q = i + 1; q < n; ++q) s -= L[(size_t)q * n + i] * col[q];
+      col[i] = s / L[(size_t)i * n + i];
+    }
+    for (int i = 0; i < n; ++i) inv[(size_t)c * n + i] = col[i];
+  }
+  return true;
+}
+
+void host_cr_blocks(const Level& L, const std::vector<double>& nu, double beta, double eps_inv,
+                    std::vector<double>& B) {
+  B.resize((size_t)L.nc * 36);
+  for (int c = 0; c < L.nc; ++c) {
+    CellGeom g;
+    cell_geom(L.X.data(), L.cells.data() + 3 * c, g);
+    cr_block(g, nu[c], beta, eps_inv, &B[(size_t)c * 36]);
+  }
+}
+
+
+void level_viscosities(const std::vector<Level>& lv, const std::vector<double>& nu_fine,
+                       std::vector<std::vector<double>>& nu) {
+  const int J = (int)lv.size();
+  nu.assign(J, {});
+  nu[J - 1] = nu_fine;
+  for (int l = J - 1; l > 0; --l) {
+    nu[l - 1].assign(lv[l - 1].nc, 0.0);
+    for (int c = 0; c < lv[l - 1].nc; ++c)
+      nu[l - 1][c] = 0.25 * (nu[l][4 * c] + nu[l][4 * c + 1] + nu[l][4 * c + 2] + nu[l][4 * c + 3]);
+  }
+}
+
+bool stabilised_transfer(const Level& Cl, const Level& Fl, const Averaging& Av,
+                         const std::vector<double>& nu_f, double beta, double eps_inv, CSR& Pc, CSR& Rc) {
+  std::vector<double> B;
+  host_cr_blocks(Fl, nu_f, beta, eps_inv, B);
+  const int nfd = 2 * Fl.nint, ncd = 2 * Cl.nint;
+  std::vector<std::map<int, double>> rows(nfd);
+  for (int r = 0; r < nfd; ++r)
+    for (int q = Av.row_ptr[r]; q < Av.row_ptr[r + 1]; ++q) rows[r][Av.col[q]] += Av.val[q];
+  std::vector<std::map<int, double>> P(rows);
+  // harmonic correction inside every coarse cell: rows of the interior fine
+  // DOFs become I - A_TT^-1 (A I)_T
+  for (int T = 0; T < Cl.nc; ++T) {
+    int inner[3];
+    for (int i = 0; i < 3; ++i) inner[i] = Av.inner_facets[3 * T + i];
+    auto pos_of = [&](int fi) {
+      for (int i = 0; i < 3; ++i)
+        if (inner[i] == fi) return i;
+      return -1;
+    };
+    std::vector<double> ATT(36, 0.0);
+    std::vector<std::map<int, double>> AI(6);
+    for (int ch = 0; ch < 4; ++ch) {
+      int Kc = 4 * T + ch;
+      const double* BK = &B[(size_t)Kc * 36];
+      for (int i1 = 0; i1 < 3; ++i1) {
+        int f1 = Fl.cell_dofs[3 * Kc + i1];
+        int p1 = f1 >= 0 ? pos_of(f1) : -1;
+        if (p1 < 0) continue;
+        for (int i2 = 0; i2 < 3; ++i2) {
+          int f2 = Fl.cell_dofs[3 * Kc + i2];
+          if (f2 < 0) continue;
+          int p2 = pos_of(f2);
+          for (int a = 0; a < 2; ++a)
+            for (int bb = 0; bb < 2; ++bb) {
+              double v = BK[(2 * i1 + a) * 6 + 2 * i2 + bb];
+              if (p2 >= 0) ATT[(2 * p1 + a) * 6 + 2 * p2 + bb] += v;
+              for (auto& kv : rows[2 * f2 + bb]) AI[2 * p1 + a][kv.first] += v * kv.second;
+            }
+        }
+      }
+    }
+    std::vector<double> inv;
+    if (!invert_spd(ATT, 6, inv)) return false;
+    for (int a = 0; a < 6; ++a) {
+      int fr = 2 * inner[a / 2] + a % 2;
+      for (int bb = 0; bb < 6; ++bb) {
+        double w = inv[(size_t)bb * 6 + a];
+        if (w == 0.0) continue;
+        for (auto& kv : AI[bb]) P[fr][kv.first] -= w * kv.second;
+      }
+    }
+  }
+  Pc = CSR();
+  Rc = CSR();
+  Pc.n = nfd;
+  Rc.n = ncd;
+  Pc.rp.assign(1, 0);
+  std::vector<std::vector<std::pair<int, double>>> cols(ncd);
+  for (int r = 0; r < nfd; ++r) {
+    for (auto& kv : P[r]) {
+      if (kv.second == 0.0) continue;
+      Pc.ci.push_back(kv.first);
+      Pc.v.push_back(kv.second);
+      cols[kv.first].push_back({r, kv.second});
+    }
+    Pc.rp.push_back((int)Pc.ci.size());
+  }
+  Rc.rp.assign(1, 0);
+  for (int c = 0; c < ncd; ++c) {
+    for (auto& e : cols[c]) {
+      Rc.ci.push_back(e.first);
+      Rc.v.push_back(e.second);
+    }
+    Rc.rp.push_back((int)Rc.ci.size());
+  }
+  return true;
+}
+
+bool coarse_inverse(const Level& L0, const std::vector<double>& nu0, double beta, double eps_inv,
+                    std::vector<double>& inv) {
+  std::vector<double> B;
+  host_cr_blocks(L0, nu0, beta, eps_inv, B);
+  const int n = 2 * L0.nint;
+  std::vector<double> A((size_t)n * n, 0.0);
+  for (int c = 0; c < L0.nc; ++c)
+    for (int i1 = 0; i1 < 3; ++i1) {
+      int f1 = L0.cell_dofs[3 * c + i1];
+      if (f1 < 0) continue;
+      for (int i2 = 0; i2 < 3; ++i2) {
+        int f2 = L0.cell_dofs[3 * c + i2];
+        if (f2 < 0) continue;
+        for (int a = 0; a < 2; ++a)
+          for (int bb = 0; bb < 2; ++bb)
+            A[(size_t)(2 * f1 + a) * n + 2 * f2 + bb] += B[(size_t)c * 36 + (2 * i1 + a) * 6 + 2 * i2 + bb];
+      }
+    }
+  if (n == 0) {
+    inv.clear();
+    return true;
+  }
+  return invert_spd(A, n, inv);
+}
+
+}  // namespace hdgmg

@@ -1,0 +1,476 @@
+// Device kernels of the skeleton solve (FP64).
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace hdgmg {
+
+namespace {
+
+constexpr int TPB = 256;
+
+inline int nblk(long n, int tpb = TPB) { return (int)((n + tpb - 1) / tpb); }
+
+__global__ void k_condense(QuadTables Q, const double* __restrict__ X, const int* __restrict__ cells,
+                           int c0, int nbatch, const double* __restrict__ nu, int nu_per_cell,
+                           double beta, double eps_inv, double* ws, double* S, int* status) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nbatch) return;
+  int c = c0 + t;
+  CellGeom g;
+  cell_geom(X, cells + 3 * c, g);
+  const int nK = 6 * (Q.k + 1);
+  double nuc = nu_per_cell ? nu[c] : nu[0];
+  int rc = element_local(Q, g, nuc, beta, eps_inv, EL_CONDENSE, nullptr, nullptr, 0.0,
+                         WS{ws + t, nbatch}, S + (long)c * nK * nK);
+  if (rc) atomicOr(status, 1);
+}
+
+__global__ void k_load(QuadTables Q, const double* __restrict__ X, const int* __restrict__ cells,
+                       int c0, int nbatch, const double* __restrict__ nu, int nu_per_cell,
+                       double beta, const double* __restrict__ f, double* ws, double* gK,
+                       int* status) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nbatch) return;
+  int c = c0 + t;
+  CellGeom g;
+  cell_geom(X, cells + 3 * c, g);
+  const int nK = 6 * (Q.k + 1);
+  double nuc = nu_per_cell ? nu[c] : nu[0];
+  int rc = element_local(Q, g, nuc, beta, 0.0, EL_LOAD, f + (long)c * Q.nq * 2, nullptr, 0.0,
+                         WS{ws + t, nbatch}, gK + (long)c * nK);
+  if (rc) atomicOr(status, 1);
+}
+
+__global__ void k_recover(QuadTables Q, const double* __restrict__ X, const int* __restrict__ cells,
+                          int c0, int nbatch, const double* __restrict__ nu, int nu_per_cell,
+                          double beta, const double* __restrict__ f, const double* __restrict__ lam,
+                          const double* __restrict__ p0, int m, const int* __restrict__ cell_dofs,
+                          double* ws, double* u, double* p, int* status) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nbatch) return;
+  int c = c0 + t;
+  CellGeom g;
+  cell_geom(X, cells + 3 * c, g);
+  double lk[6 * (KMAX + 1)];
+  for (int i = 0; i < 3; ++i) {
+    int d = cell_dofs[3 * c + i];
+    for (int cc = 0; cc < 2; ++cc)
+      for (int j = 0; j < m; ++j) lk[(i * 2 + cc) * m + j] = d >= 0 ? lam[((long)d * 2 + cc) * m + j] : 0.0;
+  }
+  double out[3 * NQ_MAX];
+  double nuc = nu_per_cell ? nu[c] : nu[0];
+  int rc = element_local(Q, g, nuc, beta, 0.0, EL_RECOVER, f + (long)c * Q.nq * 2, lk, p0[c],
+                         WS{ws + t, nbatch}, out);
+  if (rc) atomicOr(status, 1);
+  for (int q = 0; q < Q.nq; ++q) {
+    u[((long)c * Q.nq + q) * 2] = out[2 * q];
+    u[((long)c * Q.nq + q) * 2 + 1] = out[2 * q + 1];
+    p[(long)c * Q.nq + q] = out[2 * Q.nq + q];
+  }
+}
+
+__global__ void k_cr_blocks(const double* __restrict__ X, const int* __restrict__ cells, int nc,
+                            const double* __restrict__ nu_cells, double beta, double eps_inv,
+                            double* A) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  CellGeom g;
+  cell_geom(X, cells + 3 * c, g);
+  double B[36];
+  cr_block(g, nu_cells[c], beta, eps_inv, B);
+  for (int i = 0; i < 36; ++i) A[(long)c * 36 + i] = B[i];
+}
+
+// Assemble the principal block A_ss of every patch from the cell blocks and
+// invert it (Cholesky); one thread per patch, strided workspace.
+__global__ void k_patch_inverse(LevelView L, const int* __restrict__ pc_ptr, const int* __restrict__ pc,
+                                int npatch, int max_ns, double* ws, double* pinv, int* status) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npatch) return;
+  const int m2 = 2 * L.m;
+  const int f0 = L.pf_ptr[p], nfp = L.pf_ptr[p + 1] - f0;
+  const int ns = nfp * m2;
+  WS A{ws + p, npatch};
+  for (long i = 0; i < (long)ns * ns; ++i) A[i] = 0.0;
+  for (int q = pc_ptr[p]; q < pc_ptr[p + 1]; ++q) {
+    int K = pc[q];
+    int pos[3];
+    for (int i = 0; i < 3; ++i) {
+      pos[i] = -1;
+      int d = L.cell_dofs[3 * K + i];
+      for (int a = 0; a < nfp && d >= 0; ++a)
+        if (L.pf[f0 + a] == d) pos[i] = a;
+    }
+    const double* SK = L.S + (long)K * L.nK * L.nK;
+    for (int i1 = 0; i1 < 3; ++i1) {
+      if (pos[i1] < 0) continue;
+      for (int i2 = 0; i2 < 3; ++i2) {
+        if (pos[i2] < 0) continue;
+        for (int r1 = 0; r1 < m2; ++r1)
+          for (int r2 = 0; r2 < m2; ++r2)
+            A[(long)(pos[i1] * m2 + r1) * ns + pos[i2] * m2 + r2] +=
+                SK[(long)(i1 * m2 + r1) * L.nK + i2 * m2 + r2];
+      }
+    }
+  }
+  // Cholesky (lower, in place)
+  for (int j = 0; j < ns; ++j) {
+    double d = A[(long)j * ns + j];
+    for (int q = 0; q < j; ++q) d -= A[(long)j * ns + q] * A[(long)j * ns + q];
+    if (!(d > 0)) {
+      atomicOr(status, 2);
+      return;
+    }
+    d = sqrt(d);
+    A[(long)j * ns + j] = d;
+    for (int i = j + 1; i < ns; ++i) {
+      double s = A[(long)i * ns + j];
+      for (int q = 0; q < j; ++q) s -= A[(long)i * ns + q] * A[(long)j * ns + q];
+      A[(long)i * ns + j] = s / d;
+    }
+  }
+  double* out = pinv + L.pinv_off[p];
+  for (int c = 0; c < ns; ++c) {
+    double* col = out + (long)c * ns;  // column c of the inverse
+    for (int i = 0; i < ns; ++i) {
+      double s = (i == c) ? 1.0 : 0.0;
+      for (int q = 0; q < i; ++q) s -= A[(long)i * ns + q] * col[q];
+      col[i] = s / A[(long)i * ns + i];
+    }
+    for (int i = ns - 1; i >= 0; --i) {
+      double s = col[i];
+      for (int q = i + 1; q < ns; ++q) s -= A[(long)q * ns + i] * col[q];
+      col[i] = s / A[(long)i * ns + i];
+    }
+  }
+}
+
+// Row (facet fi, local row rr) of A x: sum over the two cells of fi.
+__device__ inline double row_dot(const LevelView& L, int fi, int rr, const double* __restrict__ x) {
+  const int m2 = 2 * L.m;
+  double acc = 0.0;
+  for (int s = 0; s < 2; ++s) {
+    int K = L.fcell[2 * fi + s];
+    int i = L.floc[2 * fi + s];
+    const double* row = L.S + ((long)K * L.nK + i * m2 + rr) * L.nK;
+    for (int i2 = 0; i2 < 3; ++i2) {
+      int d = L.cell_dofs[3 * K + i2];
+      if (d < 0) continue;
+      const double* xd = x + (long)d * m2;
+      const double* rw = row + i2 * m2;
+      for (int c = 0; c < m2; ++c) acc += rw[c] * xd[c];
+    }
+  }
+  return acc;
+}
+
+__global__ void k_apply(LevelView L, const double* __restrict__ x, double* __restrict__ y,
+                        double alpha, const double* __restrict__ b) {
+  long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int m2 = 2 * L.m;
+  if (t >= (long)L.nint * m2) return;
+  int fi = (int)(t / m2), rr = (int)(t % m2);
+  double v = alpha * row_dot(L, fi, rr, x);
+  y[t] = b ? b[t] + v : v;
+}
+
+__global__ void k_gather_cells(LevelView L, const double* __restrict__ vK, double* __restrict__ y) {
+  long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int m2 = 2 * L.m;
+  if (t >= (long)L.nint * m2) return;
+  int fi = (int)(t / m2), rr = (int)(t % m2);
+  double acc = 0.0;
+  for (int s = 0; s < 2; ++s) {
+    int K = L.fcell[2 * fi + s], i = L.floc[2 * fi + s];
+    acc += vK[(long)K * L.nK + i * m2 + rr];
+  }
+  y[t] = acc;
+}
+
+// Block Gauss-Seidel step on the patches [p0, p1) of one colour: one
+// wavefront per patch.  x_s += (A_ss)^-1 (b - A x)_s.  Patches of a colour
+// share no cell, so their reads of x never see a same-phase write.
+__global__ void __launch_bounds__(64) k_gs(LevelView L, int p0, double* x, const double* __restrict__ b) {
+  __shared__ double res[GS_MAX_NS];
+  const int p = p0 + blockIdx.x;
+  const int m2 = 2 * L.m;
+  const int f0 = L.pf_ptr[p], nfp = L.pf_ptr[p + 1] - f0;
+  const int ns = nfp * m2;
+  for (int t = threadIdx.x; t < ns; t += blockDim.x) {
+    int fi = L.pf[f0 + t / m2], rr = t % m2;
+    long d = (long)fi * m2 + rr;
+    res[t] = b[d] - row_dot(L, fi, rr, x);
+  }
+  __syncthreads();
+  const double* Ai = L.pinv + L.pinv_off[p];
+  double dlt[GS_MAX_NS / 64];
+  int cnt = 0;
+  for (int t = threadIdx.x; t < ns; t += blockDim.x, ++cnt) {
+    double s = 0.0;
+    for (int j = 0; j < ns; ++j) s += Ai[(long)j * ns + t] * res[j];
+    dlt[cnt] = s;
+  }
+  __syncthreads();
+  cnt = 0;
+  for (int t = threadIdx.x; t < ns; t += blockDim.x, ++cnt) {
+    int fi = L.pf[f0 + t / m2], rr = t % m2;
+    x[(long)fi * m2 + rr] += dlt[cnt];
+  }
+}
+
+__global__ void k_mode0_extract(int nint, int m, const double* __restrict__ r, double* __restrict__ g0) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 2 * nint) return;
+  g0[t] = r[(long)t * m];
+}
+
+__global__ void k_mode0_add(int nint, int m, const double* __restrict__ u0, double* __restrict__ x) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 2 * nint) return;
+  x[(long)t * m] += u0[t];
+}
+
+__global__ void k_spmv(int nrows, const int* __restrict__ rp, const int* __restrict__ ci,
+                       const double* __restrict__ v, const double* __restrict__ x, double* y,
+                       double beta_y) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  double s = 0.0;
+  for (int q = rp[r]; q < rp[r + 1]; ++q) s += v[q] * x[ci[q]];
+  y[r] = beta_y == 0.0 ? s : beta_y * y[r] + s;
+}
+
+__global__ void k_gemv_dense(int n, const double* __restrict__ A, const double* __restrict__ x,
+                             double* __restrict__ y) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  double s = 0.0;
+  for (int c = 0; c < n; ++c) s += A[(long)c * n + r] * x[c];  // column-major
+  y[r] = s;
+}
+
+__global__ void k_fill(long n, double v, double* x) {
+  long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) x[t] = v;
+}
+
+__global__ void k_copy(long n, const double* __restrict__ x, double* __restrict__ y) {
+  long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) y[t] = x[t];
+}
+
+__device__ inline double block_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ void k_dot(long n, const double* __restrict__ x, const double* __restrict__ y, double* part) {
+  __shared__ double sh[TPB];
+  double s = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    s += x[i] * y[i];
+  double r = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = r;
+}
+
+__global__ void k_dot2(long n, const double* __restrict__ z, const double* __restrict__ r,
+                       const double* __restrict__ r2, double* part) {
+  __shared__ double sh[TPB];
+  double s1 = 0.0, s2 = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    s1 += z[i] * r[i];
+    s2 += z[i] * r2[i];
+  }
+  double a = block_sum(s1, sh);
+  double b = block_sum(s2, sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = a;
+    part[gridDim.x + blockIdx.x] = b;
+  }
+}
+
+__global__ void k_finalize(const double* __restrict__ part, int nblocks, int nvals, double* sc, int slot0) {
+  __shared__ double sh[TPB];
+  for (int v = 0; v < nvals; ++v) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nblocks; i += blockDim.x) s += part[(long)v * nblocks + i];
+    double r = block_sum(s, sh);
+    if (threadIdx.x == 0) sc[slot0 + v] = r;
+  }
+}
+
+__global__ void k_fcg_xr(long n, double* x, double* r, double* r_old, const double* __restrict__ p,
+                         const double* __restrict__ q, const double* __restrict__ sc, double* part) {
+  __shared__ double sh[TPB];
+  const double alpha = sc[SC_ZR] / sc[SC_PQ];
+  double s = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    x[i] += alpha * p[i];
+    double ri = r[i];
+    r_old[i] = ri;
+    ri -= alpha * q[i];
+    r[i] = ri;
+    s += ri * ri;
+  }
+  double t = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ void k_fcg_p(long n, double* p, const double* __restrict__ z, const double* __restrict__ sc) {
+  const double beta = (sc[SC_ZRN] - sc[SC_ZRO]) / sc[SC_ZR];
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    p[i] = z[i] + beta * p[i];
+}
+
+__global__ void k_scalar_move(double* sc, int from, int to) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) sc[to] = sc[from];
+}
+
+__global__ void k_uzawa_rhs(int nint, int m, const double* __restrict__ g, const double* __restrict__ fdiv,
+                            const int* __restrict__ fcell, const double* __restrict__ p0, double* b) {
+  long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)nint * 2 * m) return;
+  double v = g[t];
+  if (t % (2 * m) == 0) {
+    int fi = (int)(t / (2 * m));
+    v += fdiv[2 * fi] * p0[fcell[2 * fi]] + fdiv[2 * fi + 1] * p0[fcell[2 * fi + 1]];
+  }
+  b[t] = v;
+}
+
+__global__ void k_uzawa_update(int nc, int m, const int* __restrict__ cell_dofs, const double* __restrict__ cdiv,
+                               const double* __restrict__ area, const double* __restrict__ lam,
+                               double eps_inv, double* p0, double* part) {
+  __shared__ double sh[TPB];
+  double s1 = 0.0, s2 = 0.0;
+  for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += (long)gridDim.x * blockDim.x) {
+    double dv = 0.0;
+    for (int i = 0; i < 3; ++i) {
+      int d = cell_dofs[3 * c + i];
+      if (d >= 0) dv += cdiv[3 * c + i] * lam[(long)d * 2 * m];
+    }
+    double dp = -eps_inv * dv / area[c];
+    double pn = p0[c] + dp;
+    p0[c] = pn;
+    s1 += area[c] * dp * dp;
+    s2 += area[c] * pn * pn;
+  }
+  double a = block_sum(s1, sh);
+  double b = block_sum(s2, sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = a;
+    part[gridDim.x + blockIdx.x] = b;
+  }
+}
+
+}  // namespace
+
+void launch_condense(hipStream_t st, const QuadTables& Q, const double* X, const int* cells, int c0,
+                     int nbatch, const double* nu, int nu_per_cell, double beta, double eps_inv,
+                     double* ws, double* S, int* status) {
+  hipLaunchKernelGGL(k_condense, dim3(nblk(nbatch, 64)), dim3(64), 0, st, Q, X, cells, c0, nbatch, nu,
+                     nu_per_cell, beta, eps_inv, ws, S, status);
+}
+void launch_load(hipStream_t st, const QuadTables& Q, const double* X, const int* cells, int c0,
+                 int nbatch, const double* nu, int nu_per_cell, double beta, const double* f,
+                 double* ws, double* gK, int* status) {
+  hipLaunchKernelGGL(k_load, dim3(nblk(nbatch, 64)), dim3(64), 0, st, Q, X, cells, c0, nbatch, nu,
+                     nu_per_cell, beta, f, ws, gK, status);
+}
+void launch_recover(hipStream_t st, const QuadTables& Q, const double* X, const int* cells, int c0,
+                    int nbatch, const double* nu, int nu_per_cell, double beta, const double* f,
+                    const double* lam, const double* p0, int m, const int* cell_dofs, double* ws,
+                    double* u, double* p, int* status) {
+  hipLaunchKernelGGL(k_recover, dim3(nblk(nbatch, 64)), dim3(64), 0, st, Q, X, cells, c0, nbatch, nu,
+                     nu_per_cell, beta, f, lam, p0, m, cell_dofs, ws, u, p, status);
+}
+void launch_cr_blocks(hipStream_t st, const double* X, const int* cells, int nc, const double* nu_cells,
+                      double beta, double eps_inv, double* A) {
+  hipLaunchKernelGGL(k_cr_blocks, dim3(nblk(nc)), dim3(TPB), 0, st, X, cells, nc, nu_cells, beta,
+                     eps_inv, A);
+}
+void launch_patch_inverse(hipStream_t st, LevelView L, const int* pc_ptr, const int* pc, int npatch,
+                          int max_ns, double* ws, double* pinv, int* status) {
+  if (npatch <= 0) return;
+  hipLaunchKernelGGL(k_patch_inverse, dim3(nblk(npatch, 64)), dim3(64), 0, st, L, pc_ptr, pc, npatch,
+                     max_ns, ws, pinv, status);
+}
+void launch_apply(hipStream_t st, LevelView L, const double* x, double* y, double alpha, const double* b) {
+  long n = (long)L.nint * 2 * L.m;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_apply, dim3(nblk(n)), dim3(TPB), 0, st, L, x, y, alpha, b);
+}
+void launch_gather_cells(hipStream_t st, LevelView L, const double* vK, double* y) {
+  long n = (long)L.nint * 2 * L.m;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_gather_cells, dim3(nblk(n)), dim3(TPB), 0, st, L, vK, y);
+}
+void launch_gs(hipStream_t st, LevelView L, int p0, int p1, double* x, const double* b) {
+  if (p1 <= p0) return;
+  hipLaunchKernelGGL(k_gs, dim3(p1 - p0), dim3(64), 0, st, L, p0, x, b);
+}
+void launch_mode0_extract(hipStream_t st, int nint, int m, const double* r, double* g0) {
+  if (nint <= 0) return;
+  hipLaunchKernelGGL(k_mode0_extract, dim3(nblk(2L * nint)), dim3(TPB), 0, st, nint, m, r, g0);
+}
+void launch_mode0_add(hipStream_t st, int nint, int m, const double* u0, double* x) {
+  if (nint <= 0) return;
+  hipLaunchKernelGGL(k_mode0_add, dim3(nblk(2L * nint)), dim3(TPB), 0, st, nint, m, u0, x);
+}
+void launch_spmv(hipStream_t st, int nrows, const int* rp, const int* ci, const double* v, const double* x,
+                 double* y, double beta_y) {
+  if (nrows <= 0) return;
+  hipLaunchKernelGGL(k_spmv, dim3(nblk(nrows)), dim3(TPB), 0, st, nrows, rp, ci, v, x, y, beta_y);
+}
+void launch_gemv_dense(hipStream_t st, int n, const double* A, const double* x, double* y) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_gemv_dense, dim3(nblk(n)), dim3(TPB), 0, st, n, A, x, y);
+}
+void launch_fill(hipStream_t st, long n, double v, double* x) {
+  if (n > 0) hipLaunchKernelGGL(k_fill, dim3(nblk(n)), dim3(TPB), 0, st, n, v, x);
+}
+void launch_copy(hipStream_t st, long n, const double* x, double* y) {
+  if (n > 0) hipLaunchKernelGGL(k_copy, dim3(nblk(n)), dim3(TPB), 0, st, n, x, y);
+}
+void launch_dot(hipStream_t st, long n, const double* x, const double* y, double* part, int nblocks) {
+  hipLaunchKernelGGL(k_dot, dim3(nblocks), dim3(TPB), 0, st, n, x, y, part);
+}
+void launch_dot2(hipStream_t st, long n, const double* z, const double* r, const double* r2, double* part,
+                 int nblocks) {
+  hipLaunchKernelGGL(k_dot2, dim3(nblocks), dim3(TPB), 0, st, n, z, r, r2, part);
+}
+void launch_finalize(hipStream_t st, const double* part, int nblocks, int nvals, double* sc, int slot0) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(TPB), 0, st, part, nblocks, nvals, sc, slot0);
+}
+void launch_fcg_xr(hipStream_t st, long n, double* x, double* r, double* r_old, const double* p,
+                   const double* q, const double* sc, double* part, int nblocks) {
+  hipLaunchKernelGGL(k_fcg_xr, dim3(nblocks), dim3(TPB), 0, st, n, x, r, r_old, p, q, sc, part);
+}
+void launch_fcg_p(hipStream_t st, long n, double* p, const double* z, const double* sc) {
+  hipLaunchKernelGGL(k_fcg_p, dim3(RED_BLOCKS), dim3(TPB), 0, st, n, p, z, sc);
+}
+void launch_scalar_move(hipStream_t st, double* sc, int from, int to) {
+  hipLaunchKernelGGL(k_scalar_move, dim3(1), dim3(64), 0, st, sc, from, to);
+}
+void launch_uzawa_rhs(hipStream_t st, int nint, int m, const double* g, const double* fdiv, const int* fcell,
+                      const double* p0, double* b) {
+  long n = (long)nint * 2 * m;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_uzawa_rhs, dim3(nblk(n)), dim3(TPB), 0, st, nint, m, g, fdiv, fcell, p0, b);
+}
+void launch_uzawa_update(hipStream_t st, int nc, int m, const int* cell_dofs, const double* cdiv,
+                         const double* area, const double* lam, double eps_inv, double* p0, double* part,
+                         int nblocks) {
+  hipLaunchKernelGGL(k_uzawa_update, dim3(nblocks), dim3(TPB), 0, st, nc, m, cell_dofs, cdiv, area, lam,
+                     eps_inv, p0, part);
+}
+
+}  // namespace hdgmg

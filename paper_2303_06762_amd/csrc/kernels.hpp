@@ -1,0 +1,77 @@
+// Device kernels of the skeleton solve (declarations shared by the host
+// orchestration).  All kernels are FP64; vectors are skeleton vectors of a
+// level with m modes per facet component (m = k+1 on the order-k level,
+// m = 1 on the lowest-order levels), indexed (F * 2 + c) * m + j.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "element.hpp"
+
+namespace hdgmg {
+
+// Level data on the device.
+struct LevelView {
+  int nc, nint, m, nK;
+  const int* cell_dofs;   // [nc][3] interior facet id or -1
+  const int* fcell;       // [nint][2] the two cells of each interior facet
+  const int* floc;        // [nint][2] local facet index in those cells
+  const double* S;        // [nc][nK][nK] cell blocks of A^eps (symmetric)
+  const int* pf_ptr;      // patch -> facets CSR
+  const int* pf;
+  const long* pinv_off;   // patch -> offset of its inverse (column-major)
+  const double* pinv;
+};
+
+// Scalars of the flexible-CG recurrence kept on the device.
+enum { SC_ZR = 0, SC_PQ, SC_RR, SC_ZRN, SC_ZRO, SC_BB, SC_DP, SC_PP, SC_N };
+
+void launch_condense(hipStream_t st, const QuadTables& Q, const double* X, const int* cells,
+                     int c0, int nbatch, const double* nu, int nu_per_cell, double beta,
+                     double eps_inv, double* ws, double* S, int* status);
+void launch_load(hipStream_t st, const QuadTables& Q, const double* X, const int* cells, int c0,
+                 int nbatch, const double* nu, int nu_per_cell, double beta, const double* f,
+                 double* ws, double* gK, int* status);
+void launch_recover(hipStream_t st, const QuadTables& Q, const double* X, const int* cells,
+                    int c0, int nbatch, const double* nu, int nu_per_cell, double beta,
+                    const double* f, const double* lam, const double* p0, int m,
+                    const int* cell_dofs, double* ws, double* u, double* p, int* status);
+void launch_cr_blocks(hipStream_t st, const double* X, const int* cells, int nc,
+                      const double* nu_cells, double beta, double eps_inv, double* A);
+void launch_patch_inverse(hipStream_t st, LevelView L, const int* pc_ptr, const int* pc,
+                          int npatch, int max_ns, double* ws, double* pinv, int* status);
+// y = alpha * A x + (b ? b : 0)
+void launch_apply(hipStream_t st, LevelView L, const double* x, double* y, double alpha,
+                  const double* b);
+// y[d] = sum over the two cells of F of per-cell vector entries (gather)
+void launch_gather_cells(hipStream_t st, LevelView L, const double* vK, double* y);
+void launch_gs(hipStream_t st, LevelView L, int p0, int p1, double* x, const double* b);
+void launch_mode0_extract(hipStream_t st, int nint, int m, const double* r, double* g0);
+void launch_mode0_add(hipStream_t st, int nint, int m, const double* u0, double* x);
+void launch_spmv(hipStream_t st, int nrows, const int* rp, const int* ci, const double* v,
+                 const double* x, double* y, double beta_y);
+void launch_gemv_dense(hipStream_t st, int n, const double* A, const double* x, double* y);
+void launch_fill(hipStream_t st, long n, double v, double* x);
+void launch_copy(hipStream_t st, long n, const double* x, double* y);
+// partial sums of x.y into part[nblocks]; finalize part into sc[slot]
+void launch_dot(hipStream_t st, long n, const double* x, const double* y, double* part,
+                int nblocks);
+void launch_dot2(hipStream_t st, long n, const double* z, const double* r, const double* r2,
+                 double* part, int nblocks);
+void launch_finalize(hipStream_t st, const double* part, int nblocks, int nvals, double* sc,
+                     int slot0);
+void launch_fcg_xr(hipStream_t st, long n, double* x, double* r, double* r_old, const double* p,
+                   const double* q, const double* sc, double* part, int nblocks);
+void launch_fcg_p(hipStream_t st, long n, double* p, const double* z, const double* sc);
+void launch_scalar_move(hipStream_t st, double* sc, int from, int to);
+// Uzawa helpers
+void launch_uzawa_rhs(hipStream_t st, int nint, int m, const double* g, const double* fdiv,
+                      const int* fcell, const double* p0, double* b);
+void launch_uzawa_update(hipStream_t st, int nc, int m, const int* cell_dofs,
+                         const double* cdiv, const double* area, const double* lam,
+                         double eps_inv, double* p0, double* part, int nblocks);
+
+constexpr int RED_BLOCKS = 512;
+// Largest vertex-patch block the Gauss-Seidel kernel holds in LDS.
+constexpr int GS_MAX_NS = 256;
+
+}  // namespace hdgmg

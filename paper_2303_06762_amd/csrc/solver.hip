@@ -1,0 +1,715 @@
+// Host orchestration of the skeleton solve and the C ABI (include/hdgmg.h).
+//
+//   setup     mesh hierarchy, skeleton topology, patches, colouring,
+//             averaging weights (host); device buffers
+//   assemble  order-k condensation and lowest-order cell blocks (device),
+//             patch inverses (device), harmonic-extension transfers and the
+//             coarsest inverse (host, FP64), uploads
+//   solve     condensed load -> AL-Uzawa { flexible CG + MG_hp } -> recovery,
+//             every vector operation on the device
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/hdgmg.h"
+#include "kernels.hpp"
+#include "host_setup.hpp"
+#include "topology.hpp"
+
+using namespace hdgmg;
+
+namespace {
+
+std::string g_setup_error;
+
+struct DevLevel {
+  int nc = 0, nint = 0, m = 1, nK = 6;
+  long ndof = 0;
+  int* cells = nullptr;
+  int* cell_dofs = nullptr;
+  int* fcell = nullptr;
+  int* floc = nullptr;
+  double* X = nullptr;
+  double* S = nullptr;
+  int* pf_ptr = nullptr;
+  int* pf = nullptr;
+  int* pc_ptr = nullptr;
+  int* pc = nullptr;
+  long* pinv_off = nullptr;
+  double* pinv = nullptr;
+  int npatch = 0, max_ns = 0;
+  long pinv_len = 0;
+  std::vector<int> colour_ptr;
+  double* nu = nullptr;  // per cell
+  double *u = nullptr, *g = nullptr, *r = nullptr;  // multigrid vectors
+  LevelView view() const {
+    LevelView v;
+    v.nc = nc;
+    v.nint = nint;
+    v.m = m;
+    v.nK = nK;
+    v.cell_dofs = cell_dofs;
+    v.fcell = fcell;
+    v.floc = floc;
+    v.S = S;
+    v.pf_ptr = pf_ptr;
+    v.pf = pf;
+    v.pinv_off = pinv_off;
+    v.pinv = pinv;
+    return v;
+  }
+};
+
+struct DevTransfer {
+  int nfine = 0, ncoarse = 0;
+  int *P_rp = nullptr, *P_ci = nullptr;
+  double* P_v = nullptr;
+  int *R_rp = nullptr, *R_ci = nullptr;
+  double* R_v = nullptr;
+};
+
+}  // namespace
+
+struct hdgmg_ctx {
+  std::string err;
+  hipStream_t st = nullptr;
+  int k = 0, J = 0;
+  double beta = 0, gamma = 0;
+  std::vector<double> nu_fine;
+  hdgmg_opts opts;
+  std::vector<Level> lv;
+  std::vector<Averaging> avg;
+  QuadTables Q;
+  DevLevel K;
+  std::vector<DevLevel> cr;
+  std::vector<DevTransfer> tr;
+  double* coarse_inv = nullptr;
+  int n0 = 0;
+  // Krylov / Uzawa vectors
+  double *x = nullptr, *r = nullptr, *r_old = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+  double *b = nullptr, *gvec = nullptr, *lam = nullptr, *p0 = nullptr;
+  double *sc = nullptr, *part = nullptr;
+  double *fdiv = nullptr, *cdiv = nullptr, *area = nullptr;
+  double* gK = nullptr;
+  double* statebuf = nullptr;  // [N_skel + n_cells] for hdgmg_solve without state
+  double* ws = nullptr;
+  size_t ws_bytes = 0;
+  int* status = nullptr;
+  bool assembled = false;
+  size_t bytes = 0;
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+#define HIPC(expr)                                                                   \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess) {                                                          \
+      ctx->err = std::string("HIP error: ") + hipGetErrorString(e_) + " at " #expr; \
+      return HDGMG_EHIP;                                                             \
+    }                                                                                \
+  } while (0)
+
+template <class T>
+hdgmg_status dalloc(hdgmg_ctx* ctx, T** p, size_t n) {
+  *p = nullptr;
+  if (n == 0) return HDGMG_OK;
+  void* v = nullptr;
+  hipError_t e = hipMalloc(&v, n * sizeof(T));
+  if (e != hipSuccess) {
+    ctx->err = "device allocation of " + std::to_string(n * sizeof(T)) + " bytes failed";
+    return HDGMG_ENOMEM;
+  }
+  ctx->allocs.push_back(v);
+  ctx->bytes += n * sizeof(T);
+  *p = (T*)v;
+  return HDGMG_OK;
+}
+
+template <class T>
+hdgmg_status upload(hdgmg_ctx* ctx, T** p, const std::vector<T>& h) {
+  hdgmg_status s = dalloc(ctx, p, h.size());
+  if (s) return s;
+  if (!h.empty()) HIPC(hipMemcpyAsync(*p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, ctx->st));
+  return HDGMG_OK;
+}
+
+#define TRY(expr)                 \
+  do {                            \
+    hdgmg_status s_ = (expr);     \
+    if (s_ != HDGMG_OK) return s_; \
+  } while (0)
+
+// ------------------------------------------------------------- device level
+hdgmg_status upload_level(hdgmg_ctx* ctx, const Level& L, int m, DevLevel& D) {
+  D.nc = L.nc;
+  D.nint = L.nint;
+  D.m = m;
+  D.nK = 6 * m;
+  D.ndof = (long)L.nint * 2 * m;
+  TRY(upload(ctx, &D.cells, L.cells));
+  TRY(upload(ctx, &D.cell_dofs, L.cell_dofs));
+  TRY(upload(ctx, &D.X, L.X));
+  std::vector<int> fc(2 * (size_t)L.nint), fl(2 * (size_t)L.nint);
+  for (int i = 0; i < L.nint; ++i) {
+    int f = L.int_facet[i];
+    for (int s = 0; s < 2; ++s) {
+      fc[2 * i + s] = L.facet_cells[2 * f + s];
+      fl[2 * i + s] = L.facet_loc[2 * f + s];
+    }
+  }
+  TRY(upload(ctx, &D.fcell, fc));
+  TRY(upload(ctx, &D.floc, fl));
+  TRY(upload(ctx, &D.pf_ptr, L.patch_facet_ptr));
+  TRY(upload(ctx, &D.pf, L.patch_facets));
+  TRY(upload(ctx, &D.pc_ptr, L.patch_cell_ptr));
+  TRY(upload(ctx, &D.pc, L.patch_cells));
+  D.npatch = (int)L.patch_vertex.size();
+  std::vector<long> off(D.npatch);
+  long tot = 0;
+  D.max_ns = 0;
+  for (int p = 0; p < D.npatch; ++p) {
+    int ns = (L.patch_facet_ptr[p + 1] - L.patch_facet_ptr[p]) * 2 * m;
+    off[p] = tot;
+    tot += (long)ns * ns;
+    D.max_ns = std::max(D.max_ns, ns);
+  }
+  D.pinv_len = tot;
+  TRY(upload(ctx, &D.pinv_off, off));
+  TRY(dalloc(ctx, &D.pinv, (size_t)tot));
+  TRY(dalloc(ctx, &D.S, (size_t)L.nc * D.nK * D.nK));
+  D.colour_ptr = L.colour_ptr;
+  TRY(dalloc(ctx, &D.u, (size_t)D.ndof));
+  TRY(dalloc(ctx, &D.g, (size_t)D.ndof));
+  TRY(dalloc(ctx, &D.r, (size_t)D.ndof));
+  return HDGMG_OK;
+}
+
+hdgmg_status check_status(hdgmg_ctx* ctx, const char* what) {
+  int h = 0;
+  HIPC(hipMemcpyAsync(&h, ctx->status, sizeof(int), hipMemcpyDeviceToHost, ctx->st));
+  HIPC(hipStreamSynchronize(ctx->st));
+  if (h) {
+    ctx->err = std::string(what) + ": singular local problem (status " + std::to_string(h) + ")";
+    return HDGMG_ENONFINITE;
+  }
+  return HDGMG_OK;
+}
+
+hdgmg_status patch_inverses(hdgmg_ctx* ctx, DevLevel& D) {
+  size_t need = (size_t)D.max_ns * D.max_ns * D.npatch * sizeof(double);
+  if (need > ctx->ws_bytes) {
+    ctx->err = "patch workspace too small";
+    return HDGMG_ENOMEM;
+  }
+  HIPC(hipMemsetAsync(ctx->status, 0, sizeof(int), ctx->st));
+  launch_patch_inverse(ctx->st, D.view(), D.pc_ptr, D.pc, D.npatch, D.max_ns, ctx->ws, D.pinv, ctx->status);
+  HIPC(hipGetLastError());
+  return check_status(ctx, "patch inverse");
+}
+
+// ------------------------------------------------------------ multigrid
+void sweep(hdgmg_ctx* ctx, DevLevel& D, double* x, const double* b, bool forward) {
+  const int nc = (int)D.colour_ptr.size() - 1;
+  for (int i = 0; i < nc; ++i) {
+    int c = forward ? i : nc - 1 - i;
+    launch_gs(ctx->st, D.view(), D.colour_ptr[c], D.colour_ptr[c + 1], x, b);
+  }
+}
+
+// Alg. 1 on lowest-order level l: u_l <- MG_h(l, g_l, u_l, m_l, q)
+void mg_h(hdgmg_ctx* ctx, int l, int m_l) {
+  DevLevel& D = ctx->cr[l];
+  if (l == 0) {
+    launch_gemv_dense(ctx->st, ctx->n0, ctx->coarse_inv, D.g, D.u);
+    return;
+  }
+  for (int s = 0; s < m_l; ++s) sweep(ctx, D, D.u, D.g, true);
+  launch_apply(ctx->st, D.view(), D.u, D.r, -1.0, D.g);
+  DevTransfer& T = ctx->tr[l];
+  DevLevel& C = ctx->cr[l - 1];
+  launch_spmv(ctx->st, T.ncoarse, T.R_rp, T.R_ci, T.R_v, D.r, C.g, 0.0);
+  launch_fill(ctx->st, C.ndof, 0.0, C.u);
+  for (int n = 0; n < ctx->opts.cycle; ++n) mg_h(ctx, l - 1, ctx->opts.vcycle_growth * m_l);
+  launch_spmv(ctx->st, T.nfine, T.P_rp, T.P_ci, T.P_v, C.u, D.u, 1.0);
+  for (int s = 0; s < m_l; ++s) sweep(ctx, D, D.u, D.g, false);
+}
+
+// Alg. 2 with zero initial guess: z = MG_hp(r)
+void mg_hp(hdgmg_ctx* ctx, const double* r, double* z) {
+  DevLevel& KL = ctx->K;
+  DevLevel& DJ = ctx->cr[ctx->J - 1];
+  if (ctx->k == 0) {
+    launch_copy(ctx->st, DJ.ndof, r, DJ.g);
+    launch_fill(ctx->st, DJ.ndof, 0.0, DJ.u);
+    mg_h(ctx, ctx->J - 1, ctx->opts.m_smooth);
+    launch_copy(ctx->st, DJ.ndof, DJ.u, z);
+    return;
+  }
+  launch_fill(ctx->st, KL.ndof, 0.0, z);
+  for (int s = 0; s < ctx->opts.m_relax; ++s) sweep(ctx, KL, z, r, true);
+  launch_apply(ctx->st, KL.view(), z, KL.r, -1.0, r);
+  launch_mode0_extract(ctx->st, KL.nint, KL.m, KL.r, DJ.g);
+  launch_fill(ctx->st, DJ.ndof, 0.0, DJ.u);
+  mg_h(ctx, ctx->J - 1, ctx->opts.m_smooth);
+  launch_mode0_add(ctx->st, KL.nint, KL.m, DJ.u, z);
+  for (int s = 0; s < ctx->opts.m_relax; ++s) sweep(ctx, KL, z, r, false);
+}
+
+// Flexible CG for A^eps x = b from x = 0.
+hdgmg_status fcg(hdgmg_ctx* ctx, const double* b, double* x, int* its_out, double* rel_out) {
+  const long n = ctx->K.ndof;
+  const int NB = RED_BLOCKS;
+  hipStream_t st = ctx->st;
+  LevelView A = ctx->K.view();
+  double hs[SC_N];
+  launch_fill(st, n, 0.0, x);
+  launch_copy(st, n, b, ctx->r);
+  launch_dot(st, n, ctx->r, ctx->r, ctx->part, NB);
+  launch_finalize(st, ctx->part, NB, 1, ctx->sc, SC_BB);
+  HIPC(hipMemcpyAsync(hs, ctx->sc, sizeof(hs), hipMemcpyDeviceToHost, st));
+  HIPC(hipStreamSynchronize(st));
+  const double r0 = std::sqrt(hs[SC_BB]);
+  if (!std::isfinite(r0)) {
+    ctx->err = "non-finite right-hand side";
+    return HDGMG_ENONFINITE;
+  }
+  const double tol = std::max(ctx->opts.rtol * r0, ctx->opts.atol);
+  if (its_out) *its_out = 0;
+  if (rel_out) *rel_out = r0 > 0 ? 1.0 : 0.0;
+  if (r0 <= tol) return HDGMG_OK;
+  mg_hp(ctx, ctx->r, ctx->z);
+  launch_dot(st, n, ctx->z, ctx->r, ctx->part, NB);
+  launch_finalize(st, ctx->part, NB, 1, ctx->sc, SC_ZR);
+  launch_copy(st, n, ctx->z, ctx->p);
+  int it = 0;
+  double rn = r0;
+  while (it < ctx->opts.max_it) {
+    launch_apply(st, A, ctx->p, ctx->q, 1.0, nullptr);
+    launch_dot(st, n, ctx->p, ctx->q, ctx->part, NB);
+    launch_finalize(st, ctx->part, NB, 1, ctx->sc, SC_PQ);
+    launch_fcg_xr(st, n, x, ctx->r, ctx->r_old, ctx->p, ctx->q, ctx->sc, ctx->part, NB);
+    launch_finalize(st, ctx->part, NB, 1, ctx->sc, SC_RR);
+    HIPC(hipMemcpyAsync(hs, ctx->sc, sizeof(hs), hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    ++it;
+    if (!std::isfinite(hs[SC_RR]) || !std::isfinite(hs[SC_PQ]) || !std::isfinite(hs[SC_ZR])) {
+      ctx->err = "non-finite value in flexible CG";
+      return HDGMG_ENONFINITE;
+    }
+    if (hs[SC_PQ] <= 0.0 || hs[SC_ZR] <= 0.0) {
+      ctx->err = "flexible CG breakdown (p.Ap <= 0 or z.r <= 0)";
+      return HDGMG_EBREAKDOWN;
+    }
+    rn = std::sqrt(hs[SC_RR]);
+    if (its_out) *its_out = it;
+    if (rel_out) *rel_out = rn / r0;
+    if (rn <= tol) return HDGMG_OK;
+    mg_hp(ctx, ctx->r, ctx->z);
+    launch_dot2(st, n, ctx->z, ctx->r, ctx->r_old, ctx->part, NB);
+    launch_finalize(st, ctx->part, NB, 2, ctx->sc, SC_ZRN);
+    launch_fcg_p(st, n, ctx->p, ctx->z, ctx->sc);
+    launch_scalar_move(st, ctx->sc, SC_ZRN, SC_ZR);
+  }
+  ctx->err = "inner solve reached max_it";
+  return HDGMG_NOT_CONVERGED;
+}
+
+hdgmg_status build_transfers(hdgmg_ctx* ctx) {
+  const double eps_inv = ctx->gamma;
+  ctx->tr.assign(ctx->J, DevTransfer());
+  std::vector<std::vector<double>> nu;
+  level_viscosities(ctx->lv, ctx->nu_fine, nu);
+  for (int l = 0; l < ctx->J; ++l) TRY(upload(ctx, &ctx->cr[l].nu, nu[l]));
+  for (int l = 1; l < ctx->J; ++l) {
+    CSR P, R;
+    if (!stabilised_transfer(ctx->lv[l - 1], ctx->lv[l], ctx->avg[l], nu[l], ctx->beta, eps_inv, P, R)) {
+      ctx->err = "singular interior block in harmonic extension";
+      return HDGMG_ENONFINITE;
+    }
+    DevTransfer& Tt = ctx->tr[l];
+    Tt.nfine = P.n;
+    Tt.ncoarse = R.n;
+    TRY(upload(ctx, &Tt.P_rp, P.rp));
+    TRY(upload(ctx, &Tt.P_ci, P.ci));
+    TRY(upload(ctx, &Tt.P_v, P.v));
+    TRY(upload(ctx, &Tt.R_rp, R.rp));
+    TRY(upload(ctx, &Tt.R_ci, R.ci));
+    TRY(upload(ctx, &Tt.R_v, R.v));
+  }
+  std::vector<double> inv;
+  if (!coarse_inverse(ctx->lv[0], nu[0], ctx->beta, eps_inv, inv)) {
+    ctx->err = "coarsest operator not positive definite";
+    return HDGMG_ENONFINITE;
+  }
+  ctx->n0 = 2 * ctx->lv[0].nint;
+  TRY(upload(ctx, &ctx->coarse_inv, inv));
+  return HDGMG_OK;
+}
+
+hdgmg_status batched(hdgmg_ctx* ctx, int nc, int k, int mode, const double* f, const double* lam,
+                     const double* p0, double* out1, double* out2) {
+  long per = element_ws_size(k);
+  long batch = std::max<long>(1, std::min<long>(nc, (long)(ctx->ws_bytes / (per * sizeof(double)))));
+  HIPC(hipMemsetAsync(ctx->status, 0, sizeof(int), ctx->st));
+  DevLevel& D = ctx->K;
+  for (long c0 = 0; c0 < nc; c0 += batch) {
+    int nb = (int)std::min<long>(batch, nc - c0);
+    if (mode == EL_CONDENSE)
+      launch_condense(ctx->st, ctx->Q, D.X, D.cells, (int)c0, nb, D.nu, 1, ctx->beta, ctx->gamma, ctx->ws,
+                      D.S, ctx->status);
+    else if (mode == EL_LOAD)
+      launch_load(ctx->st, ctx->Q, D.X, D.cells, (int)c0, nb, D.nu, 1, ctx->beta, f, ctx->ws, out1,
+                  ctx->status);
+    else
+      launch_recover(ctx->st, ctx->Q, D.X, D.cells, (int)c0, nb, D.nu, 1, ctx->beta, f, lam, p0, D.m,
+                     D.cell_dofs, ctx->ws, out1, out2, ctx->status);
+    HIPC(hipGetLastError());
+  }
+  return check_status(ctx, mode == EL_CONDENSE ? "condensation" : mode == EL_LOAD ? "load" : "recovery");
+}
+
+}  // namespace
+
+extern "C" {
+
+void hdgmg_default_opts(hdgmg_opts* o) {
+  if (!o) return;
+  o->m_relax = 1;
+  o->m_smooth = 1;
+  o->cycle = 1;
+  o->vcycle_growth = 2;
+  o->rtol = 1e-8;
+  o->atol = 1e-10;
+  o->max_it = 500;
+  o->uzawa_max = 50;
+  o->uzawa_tol = 1e-10;
+}
+
+const char* hdgmg_last_error(const hdgmg_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_setup_error.c_str();
+}
+
+void hdgmg_destroy(hdgmg_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->st) (void)hipStreamSynchronize(ctx->st);
+  for (void* p : ctx->allocs) (void)hipFree(p);
+  delete ctx;
+}
+
+hdgmg_status hdgmg_setup(const hdgmg_mesh* mesh, int k, double beta, const double* nu, int nu_len,
+                         double gamma, const hdgmg_opts* opts, void* stream, hdgmg_ctx** out) {
+  if (out) *out = nullptr;
+  g_setup_error.clear();
+  if (!mesh || !out || !nu) {
+    g_setup_error = "null argument";
+    return HDGMG_EINVAL;
+  }
+  if (mesh->dim != 2 || mesh->n_vertices < 3 || mesh->n_cells < 1 || !mesh->coords || !mesh->cells ||
+      mesh->n_refine < 0 || mesh->n_refine > 12) {
+    g_setup_error = "mesh must be 2D with >= 1 cell and 0 <= n_refine <= 12";
+    return HDGMG_EMESH;
+  }
+  if (k < 0 || k > KMAX || !(beta >= 0) || !(gamma > 0)) {
+    g_setup_error = "need 0 <= k <= 4, beta >= 0, gamma > 0";
+    return HDGMG_EINVAL;
+  }
+  long nfine = (long)mesh->n_cells << (2 * mesh->n_refine);
+  if (nu_len != 1 && nu_len != nfine) {
+    g_setup_error = "nu must have 1 or n_fine_cells entries";
+    return HDGMG_EINVAL;
+  }
+  for (int i = 0; i < nu_len; ++i)
+    if (!(nu[i] > 0) || !std::isfinite(nu[i])) {
+      g_setup_error = "nu must be positive and finite";
+      return HDGMG_EINVAL;
+    }
+  hdgmg_ctx* ctx = new hdgmg_ctx();
+  ctx->k = k;
+  ctx->beta = beta;
+  ctx->gamma = gamma;
+  hdgmg_default_opts(&ctx->opts);
+  if (opts) ctx->opts = *opts;
+  if (ctx->opts.m_relax < 0 || ctx->opts.m_smooth < 1 || ctx->opts.cycle < 1 || ctx->opts.cycle > 2 ||
+      ctx->opts.vcycle_growth < 1 || ctx->opts.max_it < 1 || ctx->opts.uzawa_max < 1 ||
+      ctx->opts.uzawa_max > HDGMG_MAX_UZAWA || !(ctx->opts.rtol >= 0) || !(ctx->opts.atol >= 0)) {
+    g_setup_error = "invalid options";
+    delete ctx;
+    return HDGMG_EINVAL;
+  }
+  ctx->st = (hipStream_t)stream;
+  ctx->J = mesh->n_refine + 1;
+  ctx->lv.resize(ctx->J);
+  Level& L0 = ctx->lv[0];
+  L0.nv = mesh->n_vertices;
+  L0.nc = mesh->n_cells;
+  L0.X.assign(mesh->coords, mesh->coords + 2 * (size_t)L0.nv);
+  L0.cells.assign(mesh->cells, mesh->cells + 3 * (size_t)L0.nc);
+  std::string e = build_level(L0);
+  for (int l = 1; l < ctx->J && e.empty(); ++l) {
+    refine(ctx->lv[l - 1], ctx->lv[l]);
+    e = build_level(ctx->lv[l]);
+  }
+  if (!e.empty()) {
+    g_setup_error = "mesh: " + e;
+    delete ctx;
+    return HDGMG_EMESH;
+  }
+  for (auto& L : ctx->lv) build_patches(L);
+  if (ctx->lv.back().max_patch_facets * 2 * (k + 1) > GS_MAX_NS) {
+    g_setup_error = "mesh: a vertex patch exceeds " + std::to_string(GS_MAX_NS) + " unknowns";
+    delete ctx;
+    return HDGMG_EMESH;
+  }
+  ctx->avg.resize(ctx->J);
+  for (int l = 1; l < ctx->J; ++l) build_averaging(ctx->lv[l - 1], ctx->lv[l], ctx->avg[l]);
+  const Level& LF = ctx->lv.back();
+  ctx->nu_fine.assign(LF.nc, nu[0]);
+  if (nu_len > 1) ctx->nu_fine.assign(nu, nu + nu_len);
+  ctx->Q = make_tables(k);
+  hdgmg_status s = HDGMG_OK;
+  auto fail = [&](hdgmg_status st) {
+    g_setup_error = ctx->err;
+    hdgmg_destroy(ctx);
+    return st;
+  };
+  if ((s = upload_level(ctx, LF, k + 1, ctx->K))) return fail(s);
+  if ((s = upload(ctx, &ctx->K.nu, ctx->nu_fine))) return fail(s);
+  ctx->cr.resize(ctx->J);
+  for (int l = 0; l < ctx->J; ++l)
+    if ((s = upload_level(ctx, ctx->lv[l], 1, ctx->cr[l]))) return fail(s);
+  const long n = ctx->K.ndof;
+  double** vecs[] = {&ctx->x, &ctx->r, &ctx->r_old, &ctx->z, &ctx->p, &ctx->q, &ctx->b, &ctx->gvec, &ctx->lam};
+  for (double** v : vecs)
+    if ((s = dalloc(ctx, v, (size_t)std::max<long>(n, 1)))) return fail(s);
+  if ((s = dalloc(ctx, &ctx->p0, (size_t)LF.nc))) return fail(s);
+  if ((s = dalloc(ctx, &ctx->sc, SC_N))) return fail(s);
+  if ((s = dalloc(ctx, &ctx->part, 4 * RED_BLOCKS))) return fail(s);
+  if ((s = dalloc(ctx, &ctx->gK, (size_t)LF.nc * 6 * (k + 1)))) return fail(s);
+  if ((s = dalloc(ctx, &ctx->status, 1))) return fail(s);
+  if ((s = dalloc(ctx, &ctx->statebuf, (size_t)(n + LF.nc)))) return fail(s);
+  // Uzawa geometry: per interior facet and side sigma|F|, per cell sigma|F| and |K|
+  std::vector<double> fdiv(2 * (size_t)LF.nint), cdiv(3 * (size_t)LF.nc), area(LF.area);
+  for (int i = 0; i < LF.nint; ++i) {
+    int f = LF.int_facet[i];
+    for (int sd = 0; sd < 2; ++sd) {
+      int c = LF.facet_cells[2 * f + sd], li = LF.facet_loc[2 * f + sd];
+      fdiv[2 * i + sd] = LF.sigma[3 * c + li] * LF.len[f];
+    }
+  }
+  for (int c = 0; c < LF.nc; ++c)
+    for (int i = 0; i < 3; ++i) {
+      int f = LF.cell_facets[3 * c + i];
+      cdiv[3 * c + i] = LF.int_id[f] >= 0 ? LF.sigma[3 * c + i] * LF.len[f] : 0.0;
+    }
+  if ((s = upload(ctx, &ctx->fdiv, fdiv))) return fail(s);
+  if ((s = upload(ctx, &ctx->cdiv, cdiv))) return fail(s);
+  if ((s = upload(ctx, &ctx->area, area))) return fail(s);
+  // workspace: element batches and patch factorisations share it
+  size_t need = 0;
+  for (auto* D : {&ctx->K}) need = std::max(need, (size_t)D->max_ns * D->max_ns * D->npatch * sizeof(double));
+  for (auto& D : ctx->cr) need = std::max(need, (size_t)D.max_ns * D.max_ns * D.npatch * sizeof(double));
+  size_t el = (size_t)element_ws_size(k) * sizeof(double) * std::min<long>(LF.nc, 16384);
+  need = std::max(need, el);
+  ctx->ws_bytes = need;
+  double* ws = nullptr;
+  if ((s = dalloc(ctx, &ws, need / sizeof(double) + 1))) return fail(s);
+  ctx->ws = ws;
+  hipError_t he = hipStreamSynchronize(ctx->st);
+  if (he != hipSuccess) {
+    ctx->err = std::string("HIP error: ") + hipGetErrorString(he);
+    return fail(HDGMG_EHIP);
+  }
+  *out = ctx;
+  return HDGMG_OK;
+}
+
+hdgmg_status hdgmg_assemble(hdgmg_ctx* ctx) {
+  if (!ctx) return HDGMG_EINVAL;
+  ctx->assembled = false;
+  TRY(batched(ctx, ctx->K.nc, ctx->k, EL_CONDENSE, nullptr, nullptr, nullptr, nullptr, nullptr));
+  TRY(patch_inverses(ctx, ctx->K));
+  TRY(build_transfers(ctx));
+  for (int l = 0; l < ctx->J; ++l) {
+    DevLevel& D = ctx->cr[l];
+    launch_cr_blocks(ctx->st, D.X, D.cells, D.nc, D.nu, ctx->beta, ctx->gamma, D.S);
+    HIPC(hipGetLastError());
+    if (l > 0) TRY(patch_inverses(ctx, D));
+  }
+  HIPC(hipStreamSynchronize(ctx->st));
+  ctx->assembled = true;
+  return HDGMG_OK;
+}
+
+hdgmg_status hdgmg_rhs(hdgmg_ctx* ctx, const double* f_qp, double* g) {
+  if (!ctx || !f_qp || !g) return HDGMG_EINVAL;
+  if (!ctx->assembled) {
+    ctx->err = "hdgmg_rhs before hdgmg_assemble";
+    return HDGMG_ESTATE;
+  }
+  TRY(batched(ctx, ctx->K.nc, ctx->k, EL_LOAD, f_qp, nullptr, nullptr, ctx->gK, nullptr));
+  launch_gather_cells(ctx->st, ctx->K.view(), ctx->gK, g);
+  HIPC(hipGetLastError());
+  HIPC(hipStreamSynchronize(ctx->st));
+  return HDGMG_OK;
+}
+
+hdgmg_status hdgmg_apply(hdgmg_ctx* ctx, const double* x, double* y) {
+  if (!ctx || !x || !y) return HDGMG_EINVAL;
+  if (!ctx->assembled) {
+    ctx->err = "hdgmg_apply before hdgmg_assemble";
+    return HDGMG_ESTATE;
+  }
+  launch_apply(ctx->st, ctx->K.view(), x, y, 1.0, nullptr);
+  HIPC(hipGetLastError());
+  HIPC(hipStreamSynchronize(ctx->st));
+  return HDGMG_OK;
+}
+
+hdgmg_status hdgmg_precondition(hdgmg_ctx* ctx, const double* r, double* z) {
+  if (!ctx || !r || !z) return HDGMG_EINVAL;
+  if (!ctx->assembled) {
+    ctx->err = "hdgmg_precondition before hdgmg_assemble";
+    return HDGMG_ESTATE;
+  }
+  mg_hp(ctx, r, z);
+  HIPC(hipGetLastError());
+  HIPC(hipStreamSynchronize(ctx->st));
+  return HDGMG_OK;
+}
+
+hdgmg_status hdgmg_inner_solve(hdgmg_ctx* ctx, const double* b, double* x, int* its, double* rel_res) {
+  if (!ctx || !b || !x) return HDGMG_EINVAL;
+  if (!ctx->assembled) {
+    ctx->err = "hdgmg_inner_solve before hdgmg_assemble";
+    return HDGMG_ESTATE;
+  }
+  hdgmg_status s = fcg(ctx, b, x, its, rel_res);
+  HIPC(hipStreamSynchronize(ctx->st));
+  return s;
+}
+
+hdgmg_status hdgmg_recover(hdgmg_ctx* ctx, const double* f_qp, const double* state, double* u_qp,
+                           double* p_qp) {
+  if (!ctx || !f_qp || !state || !u_qp || !p_qp) return HDGMG_EINVAL;
+  if (!ctx->assembled) {
+    ctx->err = "hdgmg_recover before hdgmg_assemble";
+    return HDGMG_ESTATE;
+  }
+  TRY(batched(ctx, ctx->K.nc, ctx->k, EL_RECOVER, f_qp, state, state + ctx->K.ndof, u_qp, p_qp));
+  HIPC(hipStreamSynchronize(ctx->st));
+  return HDGMG_OK;
+}
+
+hdgmg_status hdgmg_solve(hdgmg_ctx* ctx, const double* f_qp, double* u_qp, double* p_qp, double* state,
+                         hdgmg_info* info) {
+  if (!ctx || !f_qp || !u_qp || !p_qp) return HDGMG_EINVAL;
+  if (!ctx->assembled) {
+    ctx->err = "hdgmg_solve before hdgmg_assemble";
+    return HDGMG_ESTATE;
+  }
+  if (info) std::memset(info, 0, sizeof(*info));
+  hipStream_t st = ctx->st;
+  const DevLevel& KL = ctx->K;
+  TRY(hdgmg_rhs(ctx, f_qp, ctx->gvec));
+  launch_fill(st, KL.nc, 0.0, ctx->p0);
+  hdgmg_status result = HDGMG_OK;
+  for (int n = 0; n < ctx->opts.uzawa_max; ++n) {
+    launch_uzawa_rhs(st, KL.nint, KL.m, ctx->gvec, ctx->fdiv, KL.fcell, ctx->p0, ctx->b);
+    int its = 0;
+    double rel = 0.0;
+    hdgmg_status s = fcg(ctx, ctx->b, ctx->lam, &its, &rel);
+    if (s < 0) return s;
+    if (s == HDGMG_NOT_CONVERGED) result = s;
+    launch_uzawa_update(st, KL.nc, KL.m, KL.cell_dofs, ctx->cdiv, ctx->area, ctx->lam, ctx->gamma, ctx->p0,
+                        ctx->part, RED_BLOCKS);
+    launch_finalize(st, ctx->part, RED_BLOCKS, 2, ctx->sc, SC_DP);
+    double hs[SC_N];
+    HIPC(hipMemcpyAsync(hs, ctx->sc, sizeof(hs), hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    double dn = std::sqrt(hs[SC_DP]), pn = std::sqrt(hs[SC_PP]);
+    if (info) {
+      info->uzawa_steps = n + 1;
+      info->its[n] = its;
+      info->rel_res[n] = rel;
+      info->dp_l2[n] = dn;
+    }
+    if (dn <= ctx->opts.uzawa_tol * std::max(1.0, pn)) break;
+    if (n == ctx->opts.uzawa_max - 1) {
+      result = HDGMG_NOT_CONVERGED;
+      ctx->err = "AL-Uzawa reached uzawa_max";
+    }
+  }
+  if (state) {
+    launch_copy(st, KL.ndof, ctx->lam, state);
+    launch_copy(st, KL.nc, ctx->p0, state + KL.ndof);
+  }
+  // recovery reads the skeleton vector and pressure from one buffer
+  double* stt = state ? state : ctx->statebuf;
+  if (!state) {
+    launch_copy(st, KL.ndof, ctx->lam, stt);
+    launch_copy(st, KL.nc, ctx->p0, stt + KL.ndof);
+  }
+  TRY(hdgmg_recover(ctx, f_qp, stt, u_qp, p_qp));
+  HIPC(hipStreamSynchronize(st));
+  return result;
+}
+
+hdgmg_status hdgmg_query(const hdgmg_ctx* ctx, int what, int level, int64_t* value) {
+  if (!ctx || !value) return HDGMG_EINVAL;
+  const Level& LF = ctx->lv.back();
+  switch (what) {
+    case 0: *value = LF.nc; return HDGMG_OK;
+    case 1: *value = ctx->Q.nq; return HDGMG_OK;
+    case 2: *value = ctx->K.ndof; return HDGMG_OK;
+    case 3: *value = ctx->J; return HDGMG_OK;
+    case 4: *value = (int64_t)ctx->bytes; return HDGMG_OK;
+    case 5: *value = LF.nint; return HDGMG_OK;
+    case 6: *value = ctx->k; return HDGMG_OK;
+    case 7: *value = LF.ncol; return HDGMG_OK;
+    case 8:
+    case 9:
+      if (level < 0 || level >= ctx->J) return HDGMG_EINVAL;
+      *value = what == 8 ? ctx->lv[level].nc : 2L * ctx->lv[level].nint;
+      return HDGMG_OK;
+    default: return HDGMG_EINVAL;
+  }
+}
+
+hdgmg_status hdgmg_export(const hdgmg_ctx* cctx, int what, int level, void* dst, size_t bytes) {
+  hdgmg_ctx* ctx = const_cast<hdgmg_ctx*>(cctx);
+  if (!ctx || !dst) return HDGMG_EINVAL;
+  if (!ctx->assembled) {
+    ctx->err = "hdgmg_export before hdgmg_assemble";
+    return HDGMG_ESTATE;
+  }
+  const double* src = nullptr;
+  size_t n = 0;
+  if (what == 0) {
+    src = ctx->K.S;
+    n = (size_t)ctx->K.nc * ctx->K.nK * ctx->K.nK;
+  } else if (what == 1 && level >= 0 && level < ctx->J) {
+    src = ctx->cr[level].S;
+    n = (size_t)ctx->cr[level].nc * 36;
+  } else {
+    ctx->err = "hdgmg_export: bad what/level";
+    return HDGMG_EINVAL;
+  }
+  if (bytes < n * sizeof(double)) {
+    ctx->err = "hdgmg_export: destination too small";
+    return HDGMG_EINVAL;
+  }
+  HIPC(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->st));
+  HIPC(hipStreamSynchronize(ctx->st));
+  return HDGMG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,204 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+FP64 throughout.  Bars: cell blocks, loads, applies and single
+preconditioner applications to 1e-10 relative (round-off level); inner and
+full solves to 1e-10 relative with iteration counts within +-1 of the
+oracle's (same colour order, sweeps, Krylov recurrence and stopping rule).
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import mesh, hdg, cr, solver
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _note(msg):
+    print(msg, flush=True)
+
+
+def jittered_square(n, seed, amp=0.2):
+    """Structured n x n triangulation with interior vertices moved by up to
+    amp * h in each direction (seeded), giving general triangles."""
+    c, t = synth.kuhn_square(n)
+    h = 1.0 / n
+    inner = (c[:, 0] > 0) & (c[:, 0] < 1) & (c[:, 1] > 0) & (c[:, 1] < 1)
+    d = synth.uniform_pm1(seed, 7, c.shape) * amp * h
+    c = c.copy()
+    c[inner] += d[inner]
+    return c, t
+
+
+_ORACLES = {}
+
+
+def oracle_setup(key, coords, cells, n_refine, k, nu, beta, gamma, **kw):
+    if key not in _ORACLES:
+        _ORACLES[key] = solver.Setup(coords, cells, n_refine, k, nu, beta, gamma, **kw)
+    return _ORACLES[key]
+
+
+def gpu_solver(coords, cells, n_refine, k, nu, beta, gamma, **kw):
+    import paper_2303_06762_amd as hd
+    opt_names = {"m_p": "m_relax", "m_h": "m_smooth", "q": "cycle", "growth": "vcycle_growth"}
+    opts = {opt_names.get(a, a): b for a, b in kw.items()}
+    s = hd.Solver(coords, cells, n_refine, k, beta, nu, gamma, **opts)
+    s.assemble()
+    return s
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+CASES = {
+    # name: (coords, cells, n_refine, k, nu, beta, gamma, solver kwargs)
+    "k0": (lambda: synth.kuhn_square(4), 1, 0, 1.0, 1.0, 1e2, {}),
+    "k1": (lambda: synth.kuhn_square(4), 1, 1, 1.0, 1.0, 1e2, {}),
+    "k2": (lambda: synth.kuhn_square(4), 1, 2, 1.0, 1.0, 1e2, {}),
+    "k3": (lambda: synth.kuhn_square(4), 1, 3, 1.0, 1.0, 1e2, {}),
+    "k4": (lambda: synth.kuhn_square(4), 1, 4, 1.0, 1.0, 1e2, {}),
+    "beta0_gamma1e4": (lambda: synth.kuhn_square(4), 1, 2, 1.0, 0.0, 1e4, {}),
+    "jittered_k2": (lambda: jittered_square(4, 3), 1, 2, 1.3, 0.5, 1e2, {}),
+    "one_level_k2": (lambda: synth.kuhn_square(4), 0, 2, 1.0, 1.0, 1e2, {}),
+    "tiny_k1": (lambda: synth.kuhn_square(1), 1, 1, 1.0, 1.0, 1e2, {}),
+    "wcycle_k1": (lambda: synth.kuhn_square(2), 2, 1, 1.0, 1.0, 1e2, dict(q=2, growth=1)),
+    "m2_k2": (lambda: synth.kuhn_square(2), 2, 2, 1.0, 1e3, 1e2, dict(m_p=2, m_h=2)),
+}
+
+
+def case(name):
+    mk, nref, k, nu, beta, gamma, kw = CASES[name]
+    c, t = mk()
+    return c, t, nref, k, nu, beta, gamma, kw
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_cell_blocks_and_apply(name):
+    c, t, nref, k, nu, beta, gamma, kw = case(name)
+    _note(f"[blocks/apply] {name}")
+    O = oracle_setup(name, c, t, nref, k, nu, beta, gamma, **kw)
+    G = gpu_solver(c, t, nref, k, nu, beta, gamma, **kw)
+    S = host(G.export(0))
+    for K, e in enumerate(O.prob.elems):
+        Se = e.S + O.eps_inv / e.area * np.outer(e.d, e.d)
+        assert rel(S[K], Se) < 1e-10, K
+    for l, lv in enumerate(O.levels):
+        B = host(G.export(1, l))
+        for K in range(lv.n_cells):
+            assert rel(B[K], cr.cell_block(lv, K, O.hier.nus[l][K], beta, O.eps_inv)) < 1e-12
+    x = synth.uniform_pm1(21, 0, (G.n_skel,))
+    y = host(G.apply(dev(x)))
+    assert rel(y, O.Aeps @ x) < 1e-10
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_rhs_and_preconditioner(name):
+    c, t, nref, k, nu, beta, gamma, kw = case(name)
+    _note(f"[rhs/precondition] {name}")
+    O = oracle_setup(name, c, t, nref, k, nu, beta, gamma, **kw)
+    G = gpu_solver(c, t, nref, k, nu, beta, gamma, **kw)
+    f = synth.source_uniform(0, 1, G.n_cells, G.n_q)[0]
+    g = host(G.rhs(dev(f)))
+    assert rel(g, O.prob.rhs(f)) < 1e-10
+    r = synth.uniform_pm1(22, 0, (G.n_skel,))
+    z = host(G.precondition(dev(r)))
+    assert rel(z, O.prec(r)) < 1e-10
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_inner_solve(name):
+    c, t, nref, k, nu, beta, gamma, kw = case(name)
+    _note(f"[inner solve] {name}")
+    O = oracle_setup(name, c, t, nref, k, nu, beta, gamma, **kw)
+    G = gpu_solver(c, t, nref, k, nu, beta, gamma, **kw)
+    f = synth.source_uniform(0, 1, G.n_cells, G.n_q)[0]
+    g = O.prob.rhs(f)
+    x_o, its_o, hist = O.inner(g)
+    x, its, relres, st = G.inner_solve(dev(g))
+    x = host(x)
+    assert st == 0
+    assert abs(its - its_o) <= 1, (its, its_o)
+    assert relres <= 1e-8 or relres * np.linalg.norm(g) <= 1e-10
+    assert np.linalg.norm(x - x_o) <= 1e-9 * np.linalg.norm(x_o)
+
+
+@pytest.mark.parametrize("name", ["k0", "k2", "beta0_gamma1e4", "jittered_k2", "one_level_k2"])
+def test_full_solve(name):
+    c, t, nref, k, nu, beta, gamma, kw = case(name)
+    _note(f"[full solve] {name}")
+    O = oracle_setup(name, c, t, nref, k, nu, beta, gamma, **kw)
+    G = gpu_solver(c, t, nref, k, nu, beta, gamma, **kw)
+    f = synth.source_uniform(0, 1, G.n_cells, G.n_q)[0]
+    ref = O.solve(f)
+    u, p, state, info, st = G.solve(dev(f))
+    assert st == 0
+    assert info["uzawa_steps"] == len(ref["its"])
+    assert all(abs(a - b) <= 1 for a, b in zip(info["its"], ref["its"])), (info["its"], ref["its"])
+    state = host(state)
+    lam, p0 = state[:G.n_skel], state[G.n_skel:]
+    assert np.linalg.norm(lam - ref["lam"]) <= 1e-10 * np.linalg.norm(ref["lam"])
+    assert np.linalg.norm(p0 - ref["p0"]) <= 1e-10 * np.linalg.norm(ref["p0"])
+    uo, po, _, _ = O.prob.recover(ref["lam"], ref["p0"], f)
+    assert np.linalg.norm(host(u) - uo) <= 1e-10 * np.linalg.norm(uo)
+    assert np.linalg.norm(host(p) - po) <= 1e-10 * np.linalg.norm(po)
+
+
+def test_config1_full_solve_matches_oracle():
+    """Structured 4x4 squares refined twice (512 cells), k = 2, nu = beta = 1,
+    gamma = 1e2, f ~ U[-1,1) per data point (seed 0), FP64 flexible CG to
+    relative residual 1e-8."""
+    c, t = synth.kuhn_square(4)
+    _note("[config1] full solve")
+    O = oracle_setup("config1", c, t, 2, 2, 1.0, 1.0, 1e2)
+    G = gpu_solver(c, t, 2, 2, 1.0, 1.0, 1e2)
+    f = synth.source_uniform(0, 1, G.n_cells, G.n_q)[0]
+    ref = O.solve(f)
+    u, p, state, info, st = G.solve(dev(f))
+    assert st == 0
+    assert all(abs(a - b) <= 1 for a, b in zip(info["its"], ref["its"]))
+    state = host(state)
+    assert np.linalg.norm(state[:G.n_skel] - ref["lam"]) <= 1e-10 * np.linalg.norm(ref["lam"])
+    uo, po, _, dv = O.prob.recover(ref["lam"], ref["p0"], f)
+    assert np.linalg.norm(host(u) - uo) <= 1e-10 * np.linalg.norm(uo)
+    assert np.linalg.norm(host(p) - po) <= 1e-10 * np.linalg.norm(po)
+
+
+def test_error_paths():
+    import paper_2303_06762_amd as hd
+    c, t = synth.kuhn_square(2)
+    with pytest.raises(hd.HdgmgError) as e:
+        hd.Solver(c, t, 1, 7, 1.0, 1.0, 1e2)
+    assert e.value.status == -1
+    bad = t.copy()
+    bad[0, 1] = bad[0, 0]
+    with pytest.raises(hd.HdgmgError) as e:
+        hd.Solver(c, bad, 1, 1, 1.0, 1.0, 1e2)
+    assert e.value.status == -2
+    s = hd.Solver(c, t, 1, 1, 1.0, 1.0, 1e2)
+    with pytest.raises(hd.HdgmgError) as e:
+        s.apply(dev(np.zeros(s.n_skel)))
+    assert e.value.status == -5
+    s.assemble()
+    f = np.full((s.n_cells, s.n_q, 2), np.nan)
+    with pytest.raises(hd.HdgmgError) as e:
+        s.solve(dev(f))
+    assert e.value.status == -7
+    opts = hd.default_opts(max_it=1)
+    s2 = hd.Solver(c, t, 1, 1, 1.0, 1.0, 1e2, opts=opts)
+    s2.assemble()
+    f = synth.source_uniform(0, 1, s2.n_cells, s2.n_q)[0]
+    _, _, _, _, st = s2.solve(dev(f))
+    assert st == 1
