@@ -176,11 +176,29 @@ hdgmg_status hdgmg_query(const hdgmg_ctx* ctx, int what, int level, int64_t* val
  *   what 0: order-k cell blocks of A^eps [n_cells][6(k+1)][6(k+1)]
  *   what 1: lowest-order cell blocks of A^eps_{0,l} on level `level`
  *           [n_cells(level)][6][6]
+ *   what 2: coordinates of the data points of the finest cells
+ *           [n_cells][n_q][2]
  * Local DOF order inside a block: (local facet i, component c, mode j) ->
  * (i*2 + c)*m + j, local facet i opposite the cell's i-th stored vertex.
  * `bytes` is the size of dst; EINVAL if too small. */
 hdgmg_status hdgmg_export(const hdgmg_ctx* ctx, int what, int level, void* dst,
                           size_t bytes);
+
+/* Live kernel timing for roofline measurements.  While enabled for a
+ * kernel class, every launch of that class on the context's stream is
+ * bracketed by a pair of HIP events; hdgmg_kernel_timer_read synchronises
+ * the stream and returns the summed elapsed time (ms), the number of
+ * launches and the summed algorithmic bytes of those launches (the bytes
+ * the launch must move given the stored operators: every matrix entry it
+ * uses read once, its vectors read/written once).  Enabling resets the
+ * accumulators.  Classes:
+ *   0 order-k vertex-patch Gauss-Seidel, one colour phase (Alg. 2 relaxation)
+ *   1 order-k skeleton apply y = A^eps x
+ *   2 lowest-order patch Gauss-Seidel phases, all levels (Alg. 1 smoothing)
+ *   3 whole preconditioner applications z = MG_hp(r) */
+hdgmg_status hdgmg_kernel_timer(hdgmg_ctx* ctx, int kernel_class, int enable);
+hdgmg_status hdgmg_kernel_timer_read(hdgmg_ctx* ctx, int kernel_class, double* total_ms,
+                                     int64_t* launches, double* bytes);
 
 /* Message of the last failure on ctx (or of the last failed hdgmg_setup when
  * ctx is NULL).  The pointer stays valid until the next call on ctx. */

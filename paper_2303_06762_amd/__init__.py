@@ -45,7 +45,8 @@ class HdgmgError(RuntimeError):
 
 SYMBOLS = ["hdgmg_default_opts", "hdgmg_setup", "hdgmg_assemble", "hdgmg_solve", "hdgmg_rhs",
            "hdgmg_apply", "hdgmg_precondition", "hdgmg_inner_solve", "hdgmg_recover",
-           "hdgmg_query", "hdgmg_export", "hdgmg_last_error", "hdgmg_destroy"]
+           "hdgmg_query", "hdgmg_export", "hdgmg_kernel_timer", "hdgmg_kernel_timer_read",
+           "hdgmg_last_error", "hdgmg_destroy"]
 
 
 def lib():
@@ -77,6 +78,11 @@ def lib():
     L.hdgmg_query.restype = i32
     L.hdgmg_export.argtypes = [vp, i32, i32, vp, ctypes.c_size_t]
     L.hdgmg_export.restype = i32
+    L.hdgmg_kernel_timer.argtypes = [vp, i32, i32]
+    L.hdgmg_kernel_timer.restype = i32
+    L.hdgmg_kernel_timer_read.argtypes = [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64),
+                                          ctypes.POINTER(dbl)]
+    L.hdgmg_kernel_timer_read.restype = i32
     L.hdgmg_last_error.argtypes = [vp]
     L.hdgmg_last_error.restype = ctypes.c_char_p
     L.hdgmg_destroy.argtypes = [vp]
@@ -200,6 +206,22 @@ class Solver:
         d = dict(uzawa_steps=n, its=list(info.its[:n]), rel_res=list(info.rel_res[:n]),
                  dp_l2=list(info.dp_l2[:n]))
         return u, p, state, d, st
+
+    def timer(self, kernel_class, enable=True):
+        """Enable/disable the live event timer of a kernel class (see hdgmg.h)."""
+        self._check(lib().hdgmg_kernel_timer(self._h, kernel_class, int(enable)))
+
+    def timer_read(self, kernel_class):
+        """(total ms, launches, algorithmic bytes) since the timer was enabled."""
+        ms, n, b = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+        self._check(lib().hdgmg_kernel_timer_read(self._h, kernel_class, ctypes.byref(ms),
+                                                  ctypes.byref(n), ctypes.byref(b)))
+        return ms.value, n.value, b.value
+
+    def data_points(self):
+        out = self.torch.empty((self.n_cells, self.n_q, 2), dtype=self.torch.float64, device="cuda")
+        self._check(lib().hdgmg_export(self._h, 2, 0, _ptr(out), out.numel() * 8))
+        return out
 
     def export(self, what, level=0):
         if what == 0:

@@ -69,6 +69,7 @@ struct DevLevel {
 
 struct DevTransfer {
   int nfine = 0, ncoarse = 0;
+  long nnz = 0;
   int *P_rp = nullptr, *P_ci = nullptr;
   double* P_v = nullptr;
   int *R_rp = nullptr, *R_ci = nullptr;
@@ -105,6 +106,16 @@ struct hdgmg_ctx {
   bool assembled = false;
   size_t bytes = 0;
   std::vector<void*> allocs;
+  // live kernel timers (hdgmg_kernel_timer)
+  struct KTimer {
+    bool on = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    double bytes = 0.0;
+  } timers[4];
+  // algorithmic bytes of one Gauss-Seidel colour phase, per level / colour
+  std::vector<double> relax_bytes;                // order-k level
+  std::vector<std::vector<double>> smooth_bytes;  // lowest-order levels
+  double apply_bytes = 0.0, vcycle_bytes = 0.0;
 };
 
 namespace {
@@ -147,6 +158,52 @@ hdgmg_status upload(hdgmg_ctx* ctx, T** p, const std::vector<T>& h) {
     hdgmg_status s_ = (expr);     \
     if (s_ != HDGMG_OK) return s_; \
   } while (0)
+
+// ------------------------------------------------------------- kernel timers
+int kt_begin(hdgmg_ctx* ctx, int cls) {
+  auto& T = ctx->timers[cls];
+  if (!T.on) return -1;
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess) return -1;
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return -1;
+  }
+  (void)hipEventRecord(a, ctx->st);
+  T.ev.push_back({a, b});
+  return (int)T.ev.size() - 1;
+}
+
+void kt_end(hdgmg_ctx* ctx, int cls, int idx, double bytes) {
+  if (idx < 0) return;
+  auto& T = ctx->timers[cls];
+  (void)hipEventRecord(T.ev[idx].second, ctx->st);
+  T.bytes += bytes;
+}
+
+void kt_clear(hdgmg_ctx::KTimer& T) {
+  for (auto& e : T.ev) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  T.ev.clear();
+  T.bytes = 0.0;
+}
+
+// Algorithmic bytes of one Gauss-Seidel colour phase of the current kernel:
+// per patch its inverse (ns^2 words), for every patch facet the rows of both
+// cells (2m x nK words each), the cell vectors it gathers, b_s and x_s.
+double gs_phase_bytes(const Level& L, int m, int c) {
+  const int m2 = 2 * m, nK = 6 * m;
+  double w = 0.0;
+  for (int p = L.colour_ptr[c]; p < L.colour_ptr[c + 1]; ++p) {
+    int nfp = L.patch_facet_ptr[p + 1] - L.patch_facet_ptr[p];
+    double ns = nfp * m2;
+    int ncell = L.patch_cell_ptr[p + 1] - L.patch_cell_ptr[p];
+    w += ns * ns + nfp * 2.0 * m2 * nK + ncell * (double)nK + 2.0 * ns;
+  }
+  return w * 8.0;
+}
 
 // ------------------------------------------------------------- device level
 hdgmg_status upload_level(hdgmg_ctx* ctx, const Level& L, int m, DevLevel& D) {
@@ -217,12 +274,22 @@ hdgmg_status patch_inverses(hdgmg_ctx* ctx, DevLevel& D) {
 }
 
 // ------------------------------------------------------------ multigrid
-void sweep(hdgmg_ctx* ctx, DevLevel& D, double* x, const double* b, bool forward) {
+void sweep(hdgmg_ctx* ctx, DevLevel& D, double* x, const double* b, bool forward, int level) {
   const int nc = (int)D.colour_ptr.size() - 1;
+  const int cls = level < 0 ? 0 : 2;
   for (int i = 0; i < nc; ++i) {
     int c = forward ? i : nc - 1 - i;
+    int t = kt_begin(ctx, cls);
     launch_gs(ctx->st, D.view(), D.colour_ptr[c], D.colour_ptr[c + 1], x, b);
+    kt_end(ctx, cls, t, level < 0 ? ctx->relax_bytes[c] : ctx->smooth_bytes[level][c]);
   }
+}
+
+// Skeleton apply on the order-k level, timed as class 1.
+void apply_k(hdgmg_ctx* ctx, const double* x, double* y, double alpha, const double* b) {
+  int t = kt_begin(ctx, 1);
+  launch_apply(ctx->st, ctx->K.view(), x, y, alpha, b);
+  kt_end(ctx, 1, t, ctx->apply_bytes + (b ? ctx->K.ndof * 8.0 : 0.0));
 }
 
 // Alg. 1 on lowest-order level l: u_l <- MG_h(l, g_l, u_l, m_l, q)
@@ -232,7 +299,7 @@ void mg_h(hdgmg_ctx* ctx, int l, int m_l) {
     launch_gemv_dense(ctx->st, ctx->n0, ctx->coarse_inv, D.g, D.u);
     return;
   }
-  for (int s = 0; s < m_l; ++s) sweep(ctx, D, D.u, D.g, true);
+  for (int s = 0; s < m_l; ++s) sweep(ctx, D, D.u, D.g, true, l);
   launch_apply(ctx->st, D.view(), D.u, D.r, -1.0, D.g);
   DevTransfer& T = ctx->tr[l];
   DevLevel& C = ctx->cr[l - 1];
@@ -240,11 +307,17 @@ void mg_h(hdgmg_ctx* ctx, int l, int m_l) {
   launch_fill(ctx->st, C.ndof, 0.0, C.u);
   for (int n = 0; n < ctx->opts.cycle; ++n) mg_h(ctx, l - 1, ctx->opts.vcycle_growth * m_l);
   launch_spmv(ctx->st, T.nfine, T.P_rp, T.P_ci, T.P_v, C.u, D.u, 1.0);
-  for (int s = 0; s < m_l; ++s) sweep(ctx, D, D.u, D.g, false);
+  for (int s = 0; s < m_l; ++s) sweep(ctx, D, D.u, D.g, false, l);
 }
 
 // Alg. 2 with zero initial guess: z = MG_hp(r)
+void mg_hp_body(hdgmg_ctx* ctx, const double* r, double* z);
 void mg_hp(hdgmg_ctx* ctx, const double* r, double* z) {
+  int t = kt_begin(ctx, 3);
+  mg_hp_body(ctx, r, z);
+  kt_end(ctx, 3, t, ctx->vcycle_bytes);
+}
+void mg_hp_body(hdgmg_ctx* ctx, const double* r, double* z) {
   DevLevel& KL = ctx->K;
   DevLevel& DJ = ctx->cr[ctx->J - 1];
   if (ctx->k == 0) {
@@ -255,13 +328,13 @@ void mg_hp(hdgmg_ctx* ctx, const double* r, double* z) {
     return;
   }
   launch_fill(ctx->st, KL.ndof, 0.0, z);
-  for (int s = 0; s < ctx->opts.m_relax; ++s) sweep(ctx, KL, z, r, true);
-  launch_apply(ctx->st, KL.view(), z, KL.r, -1.0, r);
+  for (int s = 0; s < ctx->opts.m_relax; ++s) sweep(ctx, KL, z, r, true, -1);
+  apply_k(ctx, z, KL.r, -1.0, r);
   launch_mode0_extract(ctx->st, KL.nint, KL.m, KL.r, DJ.g);
   launch_fill(ctx->st, DJ.ndof, 0.0, DJ.u);
   mg_h(ctx, ctx->J - 1, ctx->opts.m_smooth);
   launch_mode0_add(ctx->st, KL.nint, KL.m, DJ.u, z);
-  for (int s = 0; s < ctx->opts.m_relax; ++s) sweep(ctx, KL, z, r, false);
+  for (int s = 0; s < ctx->opts.m_relax; ++s) sweep(ctx, KL, z, r, false, -1);
 }
 
 // Flexible CG for A^eps x = b from x = 0.
@@ -269,7 +342,6 @@ hdgmg_status fcg(hdgmg_ctx* ctx, const double* b, double* x, int* its_out, doubl
   const long n = ctx->K.ndof;
   const int NB = RED_BLOCKS;
   hipStream_t st = ctx->st;
-  LevelView A = ctx->K.view();
   double hs[SC_N];
   launch_fill(st, n, 0.0, x);
   launch_copy(st, n, b, ctx->r);
@@ -293,7 +365,7 @@ hdgmg_status fcg(hdgmg_ctx* ctx, const double* b, double* x, int* its_out, doubl
   int it = 0;
   double rn = r0;
   while (it < ctx->opts.max_it) {
-    launch_apply(st, A, ctx->p, ctx->q, 1.0, nullptr);
+    apply_k(ctx, ctx->p, ctx->q, 1.0, nullptr);
     launch_dot(st, n, ctx->p, ctx->q, ctx->part, NB);
     launch_finalize(st, ctx->part, NB, 1, ctx->sc, SC_PQ);
     launch_fcg_xr(st, n, x, ctx->r, ctx->r_old, ctx->p, ctx->q, ctx->sc, ctx->part, NB);
@@ -338,6 +410,7 @@ hdgmg_status build_transfers(hdgmg_ctx* ctx) {
     DevTransfer& Tt = ctx->tr[l];
     Tt.nfine = P.n;
     Tt.ncoarse = R.n;
+    Tt.nnz = (long)P.ci.size();
     TRY(upload(ctx, &Tt.P_rp, P.rp));
     TRY(upload(ctx, &Tt.P_ci, P.ci));
     TRY(upload(ctx, &Tt.P_v, P.v));
@@ -401,6 +474,7 @@ const char* hdgmg_last_error(const hdgmg_ctx* ctx) {
 void hdgmg_destroy(hdgmg_ctx* ctx) {
   if (!ctx) return;
   if (ctx->st) (void)hipStreamSynchronize(ctx->st);
+  for (auto& T : ctx->timers) kt_clear(T);
   for (void* p : ctx->allocs) (void)hipFree(p);
   delete ctx;
 }
@@ -528,6 +602,19 @@ hdgmg_status hdgmg_setup(const hdgmg_mesh* mesh, int k, double beta, const doubl
     ctx->err = std::string("HIP error: ") + hipGetErrorString(he);
     return fail(HDGMG_EHIP);
   }
+  // algorithmic byte models of the timed kernel classes
+  {
+    const int m = k + 1, nK = 6 * m;
+    ctx->relax_bytes.resize(LF.ncol);
+    for (int c = 0; c < LF.ncol; ++c) ctx->relax_bytes[c] = gs_phase_bytes(LF, m, c);
+    ctx->smooth_bytes.resize(ctx->J);
+    for (int l = 0; l < ctx->J; ++l) {
+      ctx->smooth_bytes[l].resize(ctx->lv[l].ncol);
+      for (int c = 0; c < ctx->lv[l].ncol; ++c) ctx->smooth_bytes[l][c] = gs_phase_bytes(ctx->lv[l], 1, c);
+    }
+    // apply: every cell block once, the cell vectors it gathers, y written
+    ctx->apply_bytes = ((double)LF.nc * nK * nK + (double)LF.nc * nK + (double)ctx->K.ndof) * 8.0;
+  }
   *out = ctx;
   return HDGMG_OK;
 }
@@ -545,6 +632,29 @@ hdgmg_status hdgmg_assemble(hdgmg_ctx* ctx) {
     if (l > 0) TRY(patch_inverses(ctx, D));
   }
   HIPC(hipStreamSynchronize(ctx->st));
+  // algorithmic bytes of one MG_hp application (sum over its launches)
+  {
+    double v = 0.0;
+    const auto& o = ctx->opts;
+    if (ctx->k > 0) {
+      double sw = 0.0;
+      for (double b : ctx->relax_bytes) sw += b;
+      v += 2.0 * o.m_relax * sw + ctx->apply_bytes + ctx->K.ndof * 8.0;
+    }
+    double visits = 1.0, m_l = o.m_smooth;
+    for (int l = ctx->J - 1; l >= 1; --l) {
+      double sw = 0.0;
+      for (double b : ctx->smooth_bytes[l]) sw += b;
+      const DevLevel& D = ctx->cr[l];
+      double res = ((double)D.nc * 36 + D.nc * 6.0 + 2.0 * D.ndof) * 8.0;
+      double trn = 2.0 * (ctx->tr[l].nnz * 12.0 + (ctx->tr[l].nfine + ctx->tr[l].ncoarse) * 8.0);
+      v += visits * (2.0 * m_l * sw + res + trn);
+      visits *= o.cycle;
+      m_l *= o.vcycle_growth;
+    }
+    v += visits * (double)ctx->n0 * ctx->n0 * 8.0;
+    ctx->vcycle_bytes = v;
+  }
   ctx->assembled = true;
   return HDGMG_OK;
 }
@@ -568,7 +678,7 @@ hdgmg_status hdgmg_apply(hdgmg_ctx* ctx, const double* x, double* y) {
     ctx->err = "hdgmg_apply before hdgmg_assemble";
     return HDGMG_ESTATE;
   }
-  launch_apply(ctx->st, ctx->K.view(), x, y, 1.0, nullptr);
+  apply_k(ctx, x, y, 1.0, nullptr);
   HIPC(hipGetLastError());
   HIPC(hipStreamSynchronize(ctx->st));
   return HDGMG_OK;
@@ -663,6 +773,31 @@ hdgmg_status hdgmg_solve(hdgmg_ctx* ctx, const double* f_qp, double* u_qp, doubl
   return result;
 }
 
+hdgmg_status hdgmg_kernel_timer(hdgmg_ctx* ctx, int cls, int enable) {
+  if (!ctx || cls < 0 || cls > 3) return HDGMG_EINVAL;
+  HIPC(hipStreamSynchronize(ctx->st));
+  kt_clear(ctx->timers[cls]);
+  ctx->timers[cls].on = enable != 0;
+  return HDGMG_OK;
+}
+
+hdgmg_status hdgmg_kernel_timer_read(hdgmg_ctx* ctx, int cls, double* total_ms, int64_t* launches,
+                                     double* bytes) {
+  if (!ctx || cls < 0 || cls > 3) return HDGMG_EINVAL;
+  HIPC(hipStreamSynchronize(ctx->st));
+  auto& T = ctx->timers[cls];
+  double tot = 0.0;
+  for (auto& e : T.ev) {
+    float ms = 0.f;
+    HIPC(hipEventElapsedTime(&ms, e.first, e.second));
+    tot += ms;
+  }
+  if (total_ms) *total_ms = tot;
+  if (launches) *launches = (int64_t)T.ev.size();
+  if (bytes) *bytes = T.bytes;
+  return HDGMG_OK;
+}
+
 hdgmg_status hdgmg_query(const hdgmg_ctx* ctx, int what, int level, int64_t* value) {
   if (!ctx || !value) return HDGMG_EINVAL;
   const Level& LF = ctx->lv.back();
@@ -699,6 +834,26 @@ hdgmg_status hdgmg_export(const hdgmg_ctx* cctx, int what, int level, void* dst,
   } else if (what == 1 && level >= 0 && level < ctx->J) {
     src = ctx->cr[level].S;
     n = (size_t)ctx->cr[level].nc * 36;
+  } else if (what == 2) {
+    const Level& LF = ctx->lv.back();
+    const QuadTables& Q = ctx->Q;
+    n = (size_t)LF.nc * Q.nq * 2;
+    if (bytes < n * sizeof(double)) {
+      ctx->err = "hdgmg_export: destination too small";
+      return HDGMG_EINVAL;
+    }
+    std::vector<double> pts(n);
+    for (int c = 0; c < LF.nc; ++c) {
+      CellGeom g;
+      cell_geom(LF.X.data(), LF.cells.data() + 3 * c, g);
+      for (int q = 0; q < Q.nq; ++q) {
+        pts[((size_t)c * Q.nq + q) * 2] = g.Xs0[0] + g.J[0][0] * Q.xi[q][0] + g.J[0][1] * Q.xi[q][1];
+        pts[((size_t)c * Q.nq + q) * 2 + 1] = g.Xs0[1] + g.J[1][0] * Q.xi[q][0] + g.J[1][1] * Q.xi[q][1];
+      }
+    }
+    HIPC(hipMemcpyAsync(dst, pts.data(), n * sizeof(double), hipMemcpyHostToDevice, ctx->st));
+    HIPC(hipStreamSynchronize(ctx->st));
+    return HDGMG_OK;
   } else {
     ctx->err = "hdgmg_export: bad what/level";
     return HDGMG_EINVAL;

@@ -87,3 +87,12 @@ def trig_coefficients(seed, n_modes=4, stream=0):
     a = uniform_pm1(seed, stream, (len(modes),))
     theta = 2.0 * np.pi * uniform01(seed, stream + 1, len(modes))
     return modes, a, theta
+
+
+def trig_gradient(X, seed, n_modes=4, stream=0):
+    """Gradient at points X [..., 2] of the seeded trigonometric polynomial
+    phi(x) = sum_m a_m cos(pi m.x + theta_m) of trig_coefficients."""
+    modes, a, th = trig_coefficients(seed, n_modes, stream)
+    arg = np.pi * np.tensordot(X, modes.T, axes=([-1], [0])) + th
+    s = -np.sin(arg) * a
+    return np.pi * np.tensordot(s, modes, axes=([-1], [0]))
