@@ -88,10 +88,17 @@ typedef struct {
   int max_it;              /* inner iteration cap                          */
   int uzawa_max;           /* AL-Uzawa step cap                            */
   double uzawa_tol;        /* stop when ||p_n - p_{n-1}||_L2 <= tol*max(1,||p_n||) */
+  int coarse_dofs;         /* lowest-order levels with at most this many
+                              unknowns run MG_h inside one single-workgroup
+                              kernel (0: every level launch by launch)     */
+  int stream_dofs;         /* levels with at least this many unknowns (and
+                              vertex patches of at most 6 facets) use the
+                              streaming cell-apply / patch-relax kernels   */
 } hdgmg_opts;
 
 /* Defaults: m_p = m_h = 1, V-cycle, growth 2, rtol 1e-8, atol 1e-10,
- * max_it 500, uzawa_max 50, uzawa_tol 1e-10. */
+ * max_it 500, uzawa_max 50, uzawa_tol 1e-10, coarse_dofs 2048,
+ * stream_dofs 200000. */
 void hdgmg_default_opts(hdgmg_opts* opts);
 
 #define HDGMG_MAX_UZAWA 64
@@ -194,8 +201,9 @@ hdgmg_status hdgmg_export(const hdgmg_ctx* ctx, int what, int level, void* dst,
  * accumulators.  Classes:
  *   0 order-k vertex-patch Gauss-Seidel, one colour phase (Alg. 2 relaxation)
  *   1 order-k skeleton apply y = A^eps x
- *   2 lowest-order patch Gauss-Seidel phases, all levels (Alg. 1 smoothing)
- *   3 whole preconditioner applications z = MG_hp(r) */
+ *   2 lowest-order patch Gauss-Seidel phases launched per level (Alg. 1)
+ *   3 whole preconditioner applications z = MG_hp(r)
+ *   4 single-workgroup MG_h on the coarse levels (opts.coarse_dofs) */
 hdgmg_status hdgmg_kernel_timer(hdgmg_ctx* ctx, int kernel_class, int enable);
 hdgmg_status hdgmg_kernel_timer_read(hdgmg_ctx* ctx, int kernel_class, double* total_ms,
                                      int64_t* launches, double* bytes);

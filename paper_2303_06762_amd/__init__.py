@@ -29,7 +29,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("m_relax", ctypes.c_int), ("m_smooth", ctypes.c_int), ("cycle", ctypes.c_int),
                 ("vcycle_growth", ctypes.c_int), ("rtol", ctypes.c_double),
                 ("atol", ctypes.c_double), ("max_it", ctypes.c_int), ("uzawa_max", ctypes.c_int),
-                ("uzawa_tol", ctypes.c_double)]
+                ("uzawa_tol", ctypes.c_double), ("coarse_dofs", ctypes.c_int),
+                ("stream_dofs", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -176,8 +177,8 @@ class Solver:
         self._check(lib().hdgmg_apply(self._h, _ptr(x), _ptr(y)))
         return y
 
-    def precondition(self, r):
-        z = self._vec(self.n_skel)
+    def precondition(self, r, out=None):
+        z = self._vec(self.n_skel) if out is None else out
         self._check(lib().hdgmg_precondition(self._h, _ptr(r), _ptr(z)))
         return z
 

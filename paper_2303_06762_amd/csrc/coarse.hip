@@ -1,0 +1,201 @@
+// MG_h (Alg. 1) on the coarse lowest-order levels inside one workgroup.
+//
+// Below a few thousand unknowns a level's work is far smaller than the cost
+// of a kernel launch, while the variable V-cycle doubles the number of
+// smoothing sweeps on every coarser level.  This kernel runs the recursion
+// MG_h(top, g, u, m(top), q) -- pre-smoothing, residual, restriction, the
+// coarser visits, prolongation, post-smoothing, the exact coarsest solve --
+// with workgroup barriers between dependent phases, in the same order as the
+// level-by-level launches: block Gauss-Seidel colour by colour, forward
+// before and backward after the coarse correction.
+//
+// Latency is what matters here, so the level vectors stay in LDS, the level
+// descriptors are copied to LDS once, and every patch row carries its own
+// padded residual row and inverse row (structure-of-arrays) so that a thread
+// issues independent, coalesced loads and then works from LDS.
+#include <hip/hip_runtime.h>
+
+#include "coarse.hpp"
+
+namespace hdgmg {
+
+namespace {
+
+constexpr int CT = COARSE_THREADS;
+
+// The record of one patch row: its unknown and row, residual row, inverse row.
+template <int NS>
+struct Rec {
+  unsigned key;
+  unsigned col[COARSE_NNZ / 2];
+  double val[COARSE_NNZ];
+  double ai[NS];
+};
+
+template <int NS>
+__device__ inline void load_rec(const CoarseLevel& L, int t, Rec<NS>& r) {
+  const int nit = L.nitems;
+  r.key = L.it_key[t];
+#pragma unroll
+  for (int k = 0; k < COARSE_NNZ / 2; ++k) r.col[k] = L.it_col[k * nit + t];
+#pragma unroll
+  for (int k = 0; k < COARSE_NNZ; ++k) r.val[k] = L.it_val[k * nit + t];
+#pragma unroll
+  for (int j = 0; j < NS; ++j) r.ai[j] = j < L.ns_max ? L.it_ainv[j * nit + t] : 0.0;
+}
+
+// `sweeps` block Gauss-Seidel sweeps over the colours (forward or reversed),
+// as a flat list of batches; the next batch's records are loaded while the
+// current batch computes (they do not depend on u).
+template <int NS>
+__device__ void smooth(const CoarseLevel& L, int sweeps, bool forward, double* __restrict__ res,
+                       double* __restrict__ u, const double* __restrict__ g) {
+  const int tid = threadIdx.x;
+  const int nb = L.nbatch;
+  const int steps = sweeps * nb;
+  if (steps == 0) return;
+  auto batch_of = [&](int s) { return forward ? s % nb : L.bseq_bwd[s % nb]; };
+  Rec<NS> cur, nxt;
+  int b = batch_of(0);
+  int t = L.bitem[b] + tid;
+  bool on = t < L.bitem[b + 1];
+  if (on) load_rec<NS>(L, t, cur);
+  for (int s = 0; s < steps; ++s) {
+    bool onn = false;
+    if (s + 1 < steps) {
+      const int bn = batch_of(s + 1);
+      const int tn = L.bitem[bn] + tid;
+      onn = tn < L.bitem[bn + 1];
+      if (onn) load_rec<NS>(L, tn, nxt);
+    }
+    const int dof = cur.key & 0xffff, loc = cur.key >> 16;
+    if (on) {
+      double r = g[dof];
+#pragma unroll
+      for (int k = 0; k < COARSE_NNZ / 2; ++k) {
+        r -= cur.val[2 * k] * u[cur.col[k] & 0xffff];
+        r -= cur.val[2 * k + 1] * u[cur.col[k] >> 16];
+      }
+      res[tid] = r;
+    }
+    __syncthreads();
+    if (on) {
+      const int base = tid - loc;
+      double d = 0.0;
+#pragma unroll
+      for (int j = 0; j < NS; ++j) d += cur.ai[j] * res[base + j];
+      u[dof] += d;
+    }
+    __syncthreads();
+    cur = nxt;
+    on = onn;
+  }
+}
+
+template <int NS>
+__global__ void __launch_bounds__(CT) k_coarse_cycle(const CoarseLevel* __restrict__ Lg, int top, int m_top,
+                                                     int growth, int q, const double* __restrict__ inv0,
+                                                     int n0) {
+  extern __shared__ double smem[];
+  __shared__ CoarseLevel Ls[COARSE_MAX_LEVELS];
+  const int tid = threadIdx.x;
+  double* res = smem;  // [CT + NS], the tail stays zero
+  for (int i = tid; i < CT + NS; i += CT) res[i] = 0.0;
+  if (tid <= top) Ls[tid] = Lg[tid];
+  __syncthreads();
+  {
+    const CoarseLevel& T = Ls[top];
+    double* u = smem + T.off_u;
+    double* g = smem + T.off_g;
+    for (int i = tid; i < T.n; i += CT) {
+      u[i] = T.u_glob[i];
+      g[i] = T.g_glob[i];
+    }
+  }
+  __syncthreads();
+  int state[COARSE_MAX_LEVELS], cnt[COARSE_MAX_LEVELS], mlev[COARSE_MAX_LEVELS];
+  mlev[top] = m_top;
+  for (int l = top - 1; l >= 0; --l) mlev[l] = mlev[l + 1] * growth;
+  int l = top;
+  state[l] = 0;
+  while (true) {
+    if (l == 0) {
+      const CoarseLevel& C = Ls[0];
+      double* u0 = smem + C.off_u;
+      const double* g0 = smem + C.off_g;
+      for (int i = tid; i < n0; i += CT) {
+        double s = 0.0;
+#pragma unroll 8
+        for (int j = 0; j < n0; ++j) s += inv0[(long)j * n0 + i] * g0[j];
+        u0[i] = s;
+      }
+      __syncthreads();
+      if (top == 0) break;
+      l = 1;
+      continue;
+    }
+    const CoarseLevel& L = Ls[l];
+    const CoarseLevel& B = Ls[l - 1];
+    double* u = smem + L.off_u;
+    double* g = smem + L.off_g;
+    double* r = smem + L.off_r;
+    double* ub = smem + B.off_u;
+    double* gb = smem + B.off_g;
+    if (state[l] == 0) {
+      smooth<NS>(L, mlev[l], true, res, u, g);
+      for (int i = tid; i < L.n; i += CT) {
+        double s = g[i];
+#pragma unroll
+        for (int k = 0; k < COARSE_NNZ; ++k) s -= L.rw_val[k * L.n + i] * u[L.rw_col[k * L.n + i]];
+        r[i] = s;
+      }
+      __syncthreads();
+      for (int i = tid; i < B.n; i += CT) {
+        double s = 0.0;
+        for (int k = L.R_rp[i]; k < L.R_rp[i + 1]; ++k) s += L.R_v[k] * r[L.R_ci[k]];
+        gb[i] = s;
+        ub[i] = 0.0;
+      }
+      __syncthreads();
+      state[l] = 1;
+      cnt[l] = 0;
+      state[l - 1] = 0;
+      --l;
+      continue;
+    }
+    if (++cnt[l] < q) {
+      state[l - 1] = 0;
+      --l;
+      continue;
+    }
+    for (int i = tid; i < L.n; i += CT) {
+      double s = 0.0;
+      for (int k = L.P_rp[i]; k < L.P_rp[i + 1]; ++k) s += L.P_v[k] * ub[L.P_ci[k]];
+      u[i] += s;
+    }
+    __syncthreads();
+    smooth<NS>(L, mlev[l], false, res, u, g);
+    if (l == top) break;
+    ++l;
+  }
+  {
+    const CoarseLevel& T = Ls[top];
+    const double* u = smem + T.off_u;
+    for (int i = tid; i < T.n; i += CT) T.u_glob[i] = u[i];
+  }
+}
+
+}  // namespace
+
+void launch_coarse_cycle(hipStream_t st, const CoarseLevel* Ls, int top, int m_top, int growth, int q,
+                         const double* inv0, int n0, int ns_max, int lds_doubles) {
+  size_t shm = sizeof(double) * (size_t)lds_doubles;
+  if (ns_max <= 12)
+    hipLaunchKernelGGL(k_coarse_cycle<12>, dim3(1), dim3(CT), shm, st, Ls, top, m_top, growth, q, inv0, n0);
+  else if (ns_max <= 16)
+    hipLaunchKernelGGL(k_coarse_cycle<16>, dim3(1), dim3(CT), shm, st, Ls, top, m_top, growth, q, inv0, n0);
+  else
+    hipLaunchKernelGGL(k_coarse_cycle<32>, dim3(1), dim3(CT), shm, st, Ls, top, m_top, growth, q, inv0, n0);
+}
+
+}  // namespace hdgmg

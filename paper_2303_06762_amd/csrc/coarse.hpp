@@ -1,0 +1,53 @@
+// Single-workgroup MG_h on the coarse lowest-order levels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace hdgmg {
+
+constexpr int COARSE_THREADS = 1024;
+constexpr int COARSE_MAX_LEVELS = 8;
+// A lowest-order unknown couples with the 10 unknowns of the facets of its
+// two cells (fewer next to the boundary): rows are padded to 10 entries.
+constexpr int COARSE_NNZ = 10;
+// Level vectors u, g, r of the coarse levels live in LDS: at most this many
+// doubles in total.
+constexpr int COARSE_LDS_DOUBLES = 6144;
+// Largest number of batches of one level's sweep (its schedule is staged in LDS).
+constexpr int COARSE_MAX_BATCH = 64;
+
+// One lowest-order level as seen by the coarse kernel (device pointers;
+// per-item arrays are structure-of-arrays: entry e of item t at [e*nitems+t]).
+struct CoarseLevel {
+  int n;                      // unknowns (2 per interior facet)
+  int ncol, nitems, ns_max;   // colours, patch rows, largest patch
+  int nbatch;
+  int off_u, off_g, off_r;    // LDS offsets of the level vectors (doubles)
+  const int* cb_ptr;          // [ncol+1] batch range of each colour
+  const int* bitem;           // [nbatch+1] item range of each batch
+                              // (<= COARSE_THREADS items, patch-aligned)
+  const int* bseq_bwd;        // [nbatch] batches in reverse colour order
+  const unsigned* it_key;     // [nitems] unknown | (row inside its patch) << 16
+  const unsigned* it_col;     // [COARSE_NNZ/2][nitems] residual row columns,
+                              // two 16-bit indices per word
+  const double* it_val;       // [COARSE_NNZ][nitems] residual row: values
+  const double* it_ainv;      // [ns_max][nitems] row of the patch inverse
+  const int* rw_col;          // [COARSE_NNZ][n] rows of A for the residual
+  const double* rw_val;
+  const int* R_rp;            // restriction to level l-1 (CSR, its unknowns)
+  const int* R_ci;
+  const double* R_v;
+  const int* P_rp;            // prolongation from level l-1 (CSR, these unknowns)
+  const int* P_ci;
+  const double* P_v;
+  double* u_glob;             // level vectors in HBM (used at the top level)
+  double* g_glob;
+};
+
+// u_top <- MG_h(top, g_top, u_top, m_top, q) with m(l-1) = growth m(l) on
+// levels 0..top (top <= the levels described by Ls); level 0 is solved with
+// the dense column-major inverse inv0 (n0 x n0).  lds_doubles: the dynamic
+// LDS the descriptors' offsets need.
+void launch_coarse_cycle(hipStream_t st, const CoarseLevel* Ls, int top, int m_top, int growth, int q,
+                         const double* inv0, int n0, int ns_max, int lds_doubles);
+
+}  // namespace hdgmg

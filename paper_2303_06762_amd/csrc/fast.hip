@@ -1,0 +1,237 @@
+// Streaming kernels for the skeleton apply and the vertex-patch block
+// Gauss-Seidel on levels whose patches have at most FAST_NF facets.
+//
+// Storage (structure-of-arrays so that consecutive threads read consecutive
+// addresses):
+//   Sp   cell blocks of A^eps, packed upper triangle row by row:
+//        entry e of cell K at Sp[e * nc + K]
+//   cdof per cell and local facet: 2 * interior facet + side (the side the
+//        cell occupies in that facet's cell pair), or -1 on the boundary:
+//        cdof[i * nc + K]
+//   yF   per interior facet and side, the facet's rows of S_K x_K:
+//        yF[(2 F + side) * M2 + c]
+//   pf   per patch of one colour its facets, padded with -1: pf[a * np + p]
+//   Sf   (k >= 3) cell blocks in full: entry (a, b) of cell K at
+//        Sf[(b * nc + K) * NK + a]; a thread per (cell, row)
+//   Pp   patch inverses in full, zero-padded to FAST_NF facets: entry (i, j)
+//        of patch p at Pp[(j * np + p) * NS + i]; a thread per (patch, row)
+//        so that every j-step reads one contiguous run of the workgroup
+// A Gauss-Seidel colour phase is a cell apply (y = S x for every cell) then
+// k_patch_relax (x_s += A_ss^-1 (b - y)_s for the colour's patches).
+#include <hip/hip_runtime.h>
+
+#include "fast.hpp"
+
+namespace hdgmg {
+
+namespace {
+
+template <int M2, typename TS>
+__global__ void __launch_bounds__(256) k_cell_apply(int nc, const TS* __restrict__ Sp, const int* __restrict__ cdof,
+                                                    const double* __restrict__ x, double* __restrict__ yF) {
+  constexpr int NK = 3 * M2;
+  const int K = blockIdx.x * blockDim.x + threadIdx.x;
+  if (K >= nc) return;
+  int cd[3];
+  double xl[NK], yl[NK];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) cd[i] = cdof[i * nc + K];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int c = 0; c < M2; ++c) xl[i * M2 + c] = cd[i] >= 0 ? x[(long)(cd[i] >> 1) * M2 + c] : 0.0;
+#pragma unroll
+  for (int a = 0; a < NK; ++a) yl[a] = 0.0;
+  // walk the packed entries with a running pointer (stride nc)
+  const TS* q = Sp + K;
+#pragma unroll
+  for (int a = 0; a < NK; ++a) {
+    double s = (double)*q;
+    q += nc;
+    yl[a] += s * xl[a];
+#pragma unroll
+    for (int b = a + 1; b < NK; ++b) {
+      s = (double)*q;
+      q += nc;
+      yl[a] += s * xl[b];
+      yl[b] += s * xl[a];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    if (cd[i] >= 0)
+#pragma unroll
+      for (int c = 0; c < M2; ++c) yF[(long)cd[i] * M2 + c] = yl[i * M2 + c];
+}
+
+__global__ void k_facet_sum(long n, int m2, const double* __restrict__ yF, const double* __restrict__ b,
+                            double alpha, double* __restrict__ y) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const long F = t / m2, c = t % m2;
+  const double v = alpha * (yF[(2 * F) * m2 + c] + yF[(2 * F + 1) * m2 + c]);
+  y[t] = b ? b[t] + v : v;
+}
+
+// Rows of S_K x_K with a thread per (cell, row): x_K staged in LDS.
+template <int M2, typename TS>
+__global__ void __launch_bounds__(256) k_cell_apply_rows(int nc, const TS* __restrict__ Sf,
+                                                         const int* __restrict__ cdof,
+                                                         const double* __restrict__ x, double* __restrict__ yF) {
+  constexpr int NK = 3 * M2, CPB = 256 / NK;
+  __shared__ double xs[CPB][NK];
+  const int lc = threadIdx.x / NK, a = threadIdx.x % NK;
+  const int K = blockIdx.x * CPB + lc;
+  const bool on = lc < CPB && K < nc;
+  int cd = -1;
+  if (on) {
+    const int cda = cdof[(a / M2) * nc + K];
+    xs[lc][a] = cda >= 0 ? x[(long)(cda >> 1) * M2 + a % M2] : 0.0;
+    cd = cda;
+  }
+  __syncthreads();
+  if (!on) return;
+  double y = 0.0;
+  const TS* q = Sf + (long)K * NK + a;
+#pragma unroll
+  for (int b = 0; b < NK; ++b) {
+    y += (double)*q * xs[lc][b];
+    q += (long)nc * NK;
+  }
+  if (cd >= 0) yF[(long)cd * M2 + a % M2] = y;
+}
+
+// x_s += A_ss^-1 (b - y)_s for the patches of one colour: a thread per
+// (patch, row), the patch residual shared through LDS.
+template <int M2, typename TS>
+__global__ void __launch_bounds__(256) k_patch_relax(int np, const int* __restrict__ pf, const TS* __restrict__ Pp,
+                                                     const double* __restrict__ b, const double* __restrict__ yF,
+                                                     double* __restrict__ x) {
+  constexpr int NS = FAST_NF * M2, PPB = 256 / NS;
+  __shared__ double rs[PPB][NS];
+  const int lp = threadIdx.x / NS, i = threadIdx.x % NS;
+  const int p = blockIdx.x * PPB + lp;
+  const bool on = lp < PPB && p < np;
+  int f = -1;
+  if (on) {
+    f = pf[(i / M2) * np + p];
+    const int c = i % M2;
+    rs[lp][i] = f >= 0 ? b[(long)f * M2 + c] - yF[(long)(2 * f) * M2 + c] - yF[(long)(2 * f + 1) * M2 + c] : 0.0;
+  }
+  __syncthreads();
+  if (!on) return;
+  double d = 0.0;
+  const TS* q = Pp + (long)p * NS + i;
+#pragma unroll
+  for (int j = 0; j < NS; ++j) {
+    d += (double)*q * rs[lp][j];
+    q += (long)np * NS;
+  }
+  if (f >= 0) x[(long)f * M2 + i % M2] += d;
+}
+
+// Full row-major cell blocks -> packed SoA.
+template <typename TS>
+__global__ void k_pack_cells(int nc, int nK, const double* __restrict__ S, TS* __restrict__ Sp) {
+  const int K = blockIdx.x * blockDim.x + threadIdx.x;
+  if (K >= nc) return;
+  long e = 0;
+  for (int a = 0; a < nK; ++a)
+    for (int b = a; b < nK; ++b, ++e) Sp[e * nc + K] = (TS)S[((long)K * nK + a) * nK + b];
+}
+
+// Full row-major cell blocks -> [b][K][a] SoA.
+template <typename TS>
+__global__ void k_pack_cells_full(int nc, int nK, const double* __restrict__ S, TS* __restrict__ Sf) {
+  const int K = blockIdx.x * blockDim.x + threadIdx.x;
+  if (K >= nc) return;
+  for (int a = 0; a < nK; ++a)
+    for (int b = 0; b < nK; ++b) Sf[((long)b * nc + K) * nK + a] = (TS)S[((long)K * nK + a) * nK + b];
+}
+
+// Column-major per-patch inverses (patches gp0 .. gp0+np of one colour) ->
+// [j][p][i] zero-padded to FAST_NF facets.
+template <typename TS>
+__global__ void k_pack_patches(int np, int gp0, int m2, const int* __restrict__ pf_ptr,
+                               const long* __restrict__ pinv_off, const double* __restrict__ pinv,
+                               TS* __restrict__ Pp) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  const int gp = gp0 + p;
+  const int ns = (pf_ptr[gp + 1] - pf_ptr[gp]) * m2;
+  const int NS = FAST_NF * m2;
+  const double* A = pinv + pinv_off[gp];
+  for (int j = 0; j < NS; ++j)
+    for (int i = 0; i < NS; ++i)
+      Pp[((long)j * np + p) * NS + i] = (i < ns && j < ns) ? (TS)A[(long)j * ns + i] : (TS)0;
+}
+
+inline int nblk(long n, int t = 256) { return (int)((n + t - 1) / t); }
+
+template <typename TS>
+void cell_apply_t(hipStream_t st, int m2, int nc, const TS* Sp, const int* cdof, const double* x, double* yF) {
+  switch (m2) {
+#define CASE(M)                                                                                  \
+  case M:                                                                                        \
+    hipLaunchKernelGGL((k_cell_apply<M, TS>), dim3(nblk(nc)), dim3(256), 0, st, nc, Sp, cdof, x, yF); \
+    break;
+    CASE(2) CASE(4) CASE(6)
+#undef CASE
+#define CASE(M)                                                                                        \
+  case M:                                                                                              \
+    hipLaunchKernelGGL((k_cell_apply_rows<M, TS>), dim3((nc + 256 / (3 * M) - 1) / (256 / (3 * M))),   \
+                       dim3(256), 0, st, nc, Sp, cdof, x, yF);                                         \
+    break;
+    CASE(8) CASE(10)
+#undef CASE
+  }
+}
+
+template <typename TS>
+void patch_relax_t(hipStream_t st, int m2, int np, const int* pf, const TS* Pp, const double* b, const double* yF,
+                   double* x) {
+  switch (m2) {
+#define CASE(M)                                                                                            \
+  case M:                                                                                                  \
+    hipLaunchKernelGGL((k_patch_relax<M, TS>), dim3((np + 256 / (6 * M) - 1) / (256 / (6 * M))), dim3(256), 0, \
+                       st, np, pf, Pp, b, yF, x);                                                       \
+    break;
+    CASE(2) CASE(4) CASE(6) CASE(8) CASE(10)
+#undef CASE
+  }
+}
+
+}  // namespace
+
+void launch_cell_apply(hipStream_t st, int m2, int nc, const double* Sp, const int* cdof, const double* x,
+                       double* yF) {
+  if (nc > 0) cell_apply_t<double>(st, m2, nc, Sp, cdof, x, yF);
+}
+
+void launch_facet_sum(hipStream_t st, int nint, int m2, const double* yF, const double* b, double alpha,
+                      double* y) {
+  const long n = (long)nint * m2;
+  if (n > 0) hipLaunchKernelGGL(k_facet_sum, dim3(nblk(n)), dim3(256), 0, st, n, m2, yF, b, alpha, y);
+}
+
+void launch_patch_relax(hipStream_t st, int m2, int np, const int* pf, const double* Pp, const double* b,
+                        const double* yF, double* x) {
+  if (np > 0) patch_relax_t<double>(st, m2, np, pf, Pp, b, yF, x);
+}
+
+void launch_pack_cells(hipStream_t st, int nc, int nK, const double* S, double* Sp) {
+  if (nc <= 0) return;
+  if (nK <= 18)
+    hipLaunchKernelGGL(k_pack_cells<double>, dim3(nblk(nc)), dim3(256), 0, st, nc, nK, S, Sp);
+  else
+    hipLaunchKernelGGL(k_pack_cells_full<double>, dim3(nblk(nc)), dim3(256), 0, st, nc, nK, S, Sp);
+}
+
+void launch_pack_patches(hipStream_t st, int np, int gp0, int m2, const int* pf_ptr, const long* pinv_off,
+                         const double* pinv, double* Pp) {
+  if (np > 0)
+    hipLaunchKernelGGL(k_pack_patches<double>, dim3(nblk(np)), dim3(256), 0, st, np, gp0, m2, pf_ptr, pinv_off,
+                       pinv, Pp);
+}
+
+}  // namespace hdgmg

@@ -268,6 +268,33 @@ bool stabilised_transfer(const Level& Cl, const Level& Fl, const Averaging& Av,
   return true;
 }
 
+void assemble_csr(const Level& L, const std::vector<double>& B, CSR& A) {
+  const int n = 2 * L.nint;
+  std::vector<std::map<int, double>> rows(n);
+  for (int c = 0; c < L.nc; ++c)
+    for (int i1 = 0; i1 < 3; ++i1) {
+      int f1 = L.cell_dofs[3 * c + i1];
+      if (f1 < 0) continue;
+      for (int i2 = 0; i2 < 3; ++i2) {
+        int f2 = L.cell_dofs[3 * c + i2];
+        if (f2 < 0) continue;
+        for (int a = 0; a < 2; ++a)
+          for (int b = 0; b < 2; ++b)
+            rows[2 * f1 + a][2 * f2 + b] += B[(size_t)c * 36 + (2 * i1 + a) * 6 + 2 * i2 + b];
+      }
+    }
+  A = CSR();
+  A.n = n;
+  A.rp.assign(1, 0);
+  for (int r = 0; r < n; ++r) {
+    for (auto& kv : rows[r]) {
+      A.ci.push_back(kv.first);
+      A.v.push_back(kv.second);
+    }
+    A.rp.push_back((int)A.ci.size());
+  }
+}
+
 bool coarse_inverse(const Level& L0, const std::vector<double>& nu0, double beta, double eps_inv,
                     std::vector<double>& inv) {
   std::vector<double> B;

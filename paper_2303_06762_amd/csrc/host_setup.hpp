@@ -33,6 +33,10 @@ void host_cr_blocks(const Level& L, const std::vector<double>& nu, double beta, 
 bool stabilised_transfer(const Level& C, const Level& F, const Averaging& Av,
                          const std::vector<double>& nu_f, double beta, double eps_inv, CSR& P, CSR& R);
 
+// Assembled lowest-order operator of a level from its cell blocks, as CSR
+// over the 2 n_int unknowns (columns sorted).
+void assemble_csr(const Level& L, const std::vector<double>& B, CSR& A);
+
 // Column-major inverse of the assembled coarsest operator A^eps_{0,1}.
 bool coarse_inverse(const Level& L0, const std::vector<double>& nu0, double beta, double eps_inv,
                     std::vector<double>& inv);

@@ -19,6 +19,8 @@
 #include <vector>
 
 #include "../../include/hdgmg.h"
+#include "coarse.hpp"
+#include "fast.hpp"
 #include "kernels.hpp"
 #include "host_setup.hpp"
 #include "topology.hpp"
@@ -49,6 +51,16 @@ struct DevLevel {
   std::vector<int> colour_ptr;
   double* nu = nullptr;  // per cell
   double *u = nullptr, *g = nullptr, *r = nullptr;  // multigrid vectors
+  // streaming layout (fast.hip), used when every patch has <= FAST_NF facets
+  bool fast = false;
+  double* Sp = nullptr;   // packed SoA cell blocks
+  int* cdof = nullptr;    // [3][nc] 2*facet+side or -1
+  double* yF = nullptr;   // [nint][2][2m] per-side facet rows
+  std::vector<int> npc;   // patches per colour
+  std::vector<int*> pfc;  // per colour [FAST_NF][npc] facets
+  std::vector<double*> Ppc;  // per colour packed SoA patch inverses
+  double bytes_cell = 0.0, bytes_sum = 0.0;
+  std::vector<double> bytes_relax;
   LevelView view() const {
     LevelView v;
     v.nc = nc;
@@ -81,6 +93,12 @@ struct DevTransfer {
 struct hdgmg_ctx {
   std::string err;
   hipStream_t st = nullptr;
+  hipStream_t own = nullptr;  // created when the caller passes no stream
+  // MG_hp replayed as a HIP graph for fixed (r, z) pointers
+  hipGraphExec_t vc_exec = nullptr;
+  const double* vc_r = nullptr;
+  double* vc_z = nullptr;
+  bool use_graph = true;
   int k = 0, J = 0;
   double beta = 0, gamma = 0;
   std::vector<double> nu_fine;
@@ -111,7 +129,11 @@ struct hdgmg_ctx {
     bool on = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
     double bytes = 0.0;
-  } timers[4];
+  } timers[5];
+  // single-workgroup coarse MG_h: levels 0..Lc (Lc < 0: disabled)
+  int Lc = -1;
+  CoarseLevel* coarse_desc = nullptr;
+  int coarse_lds = 0, coarse_ns = 0;
   // algorithmic bytes of one Gauss-Seidel colour phase, per level / colour
   std::vector<double> relax_bytes;                // order-k level
   std::vector<std::vector<double>> smooth_bytes;  // lowest-order levels
@@ -149,7 +171,10 @@ template <class T>
 hdgmg_status upload(hdgmg_ctx* ctx, T** p, const std::vector<T>& h) {
   hdgmg_status s = dalloc(ctx, p, h.size());
   if (s) return s;
-  if (!h.empty()) HIPC(hipMemcpyAsync(*p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, ctx->st));
+  if (!h.empty()) {
+    HIPC(hipMemcpyAsync(*p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, ctx->st));
+    HIPC(hipStreamSynchronize(ctx->st));  // h may be a temporary
+  }
   return HDGMG_OK;
 }
 
@@ -244,6 +269,47 @@ hdgmg_status upload_level(hdgmg_ctx* ctx, const Level& L, int m, DevLevel& D) {
   TRY(dalloc(ctx, &D.pinv, (size_t)tot));
   TRY(dalloc(ctx, &D.S, (size_t)L.nc * D.nK * D.nK));
   D.colour_ptr = L.colour_ptr;
+  // streaming kernels pay off on large levels; small ones keep the one-launch
+  // Gauss-Seidel phase
+  D.fast = L.max_patch_facets <= FAST_NF && (long)L.nint * 2 * m >= ctx->opts.stream_dofs;
+  if (D.fast) {
+    const int m2 = 2 * m, nK = D.nK;
+    std::vector<int> cd(3 * (size_t)L.nc, -1);
+    double ncd = 0;
+    for (int c = 0; c < L.nc; ++c)
+      for (int i = 0; i < 3; ++i) {
+        int f = L.cell_facets[3 * c + i];
+        int fi = L.int_id[f];
+        if (fi < 0) continue;
+        int side = L.facet_cells[2 * f] == c ? 0 : 1;
+        cd[(size_t)i * L.nc + c] = 2 * fi + side;
+        ncd += 1;
+      }
+    TRY(upload(ctx, &D.cdof, cd));
+    TRY(dalloc(ctx, &D.Sp, (size_t)L.nc * fast_cell_words(nK)));
+    TRY(dalloc(ctx, &D.yF, (size_t)L.nint * 2 * m2));
+    D.bytes_cell = ((double)L.nc * fast_cell_words(nK) + 2.0 * ncd * m2) * 8.0 + L.nc * 12.0;
+    D.bytes_sum = 3.0 * L.nint * m2 * 8.0;
+    const int NS = FAST_NF * m2;
+    for (int cc = 0; cc < L.ncol; ++cc) {
+      int p0 = L.colour_ptr[cc], np = L.colour_ptr[cc + 1] - p0;
+      std::vector<int> pf((size_t)FAST_NF * std::max(np, 1), -1);
+      double nfac = 0;
+      for (int p = 0; p < np; ++p) {
+        int a0 = L.patch_facet_ptr[p0 + p], na = L.patch_facet_ptr[p0 + p + 1] - a0;
+        for (int a = 0; a < na; ++a) pf[(size_t)a * np + p] = L.patch_facets[a0 + a];
+        nfac += na;
+      }
+      int* dpf;
+      double* dPp;
+      TRY(upload(ctx, &dpf, pf));
+      TRY(dalloc(ctx, &dPp, (size_t)std::max(np, 1) * NS * NS));
+      D.npc.push_back(np);
+      D.pfc.push_back(dpf);
+      D.Ppc.push_back(dPp);
+      D.bytes_relax.push_back((double)np * NS * NS * 8.0 + np * FAST_NF * 4.0 + 5.0 * nfac * m2 * 8.0);
+    }
+  }
   TRY(dalloc(ctx, &D.u, (size_t)D.ndof));
   TRY(dalloc(ctx, &D.g, (size_t)D.ndof));
   TRY(dalloc(ctx, &D.r, (size_t)D.ndof));
@@ -273,34 +339,74 @@ hdgmg_status patch_inverses(hdgmg_ctx* ctx, DevLevel& D) {
   return check_status(ctx, "patch inverse");
 }
 
+// Pack the cell blocks and patch inverses of a level into the streaming layout.
+hdgmg_status pack_fast(hdgmg_ctx* ctx, DevLevel& D) {
+  if (!D.fast) return HDGMG_OK;
+  launch_pack_cells(ctx->st, D.nc, D.nK, D.S, D.Sp);
+  for (size_t c = 0; c < D.npc.size(); ++c)
+    launch_pack_patches(ctx->st, D.npc[c], D.colour_ptr[c], 2 * D.m, D.pf_ptr, D.pinv_off, D.pinv, D.Ppc[c]);
+  HIPC(hipGetLastError());
+  return HDGMG_OK;
+}
+
 // ------------------------------------------------------------ multigrid
 void sweep(hdgmg_ctx* ctx, DevLevel& D, double* x, const double* b, bool forward, int level) {
   const int nc = (int)D.colour_ptr.size() - 1;
-  const int cls = level < 0 ? 0 : 2;
   for (int i = 0; i < nc; ++i) {
     int c = forward ? i : nc - 1 - i;
+    if (D.fast) {
+      // colour phase = cell apply (all cells) + patch relaxation (colour c)
+      int t = kt_begin(ctx, level < 0 ? 1 : 2);
+      launch_cell_apply(ctx->st, 2 * D.m, D.nc, D.Sp, D.cdof, x, D.yF);
+      kt_end(ctx, level < 0 ? 1 : 2, t, D.bytes_cell);
+      t = kt_begin(ctx, level < 0 ? 0 : 2);
+      launch_patch_relax(ctx->st, 2 * D.m, D.npc[c], D.pfc[c], D.Ppc[c], b, D.yF, x);
+      kt_end(ctx, level < 0 ? 0 : 2, t, D.bytes_relax[c]);
+    } else {
+      const int cls = level < 0 ? 0 : 2;
+      int t = kt_begin(ctx, cls);
+      launch_gs(ctx->st, D.view(), D.colour_ptr[c], D.colour_ptr[c + 1], x, b);
+      kt_end(ctx, cls, t, level < 0 ? ctx->relax_bytes[c] : ctx->smooth_bytes[level][c]);
+    }
+  }
+}
+
+// y = alpha A x + b on any level (streaming layout when available).
+void level_apply(hdgmg_ctx* ctx, DevLevel& D, const double* x, double* y, double alpha, const double* b,
+                 int cls) {
+  if (D.fast) {
     int t = kt_begin(ctx, cls);
-    launch_gs(ctx->st, D.view(), D.colour_ptr[c], D.colour_ptr[c + 1], x, b);
-    kt_end(ctx, cls, t, level < 0 ? ctx->relax_bytes[c] : ctx->smooth_bytes[level][c]);
+    launch_cell_apply(ctx->st, 2 * D.m, D.nc, D.Sp, D.cdof, x, D.yF);
+    kt_end(ctx, cls, t, D.bytes_cell);
+    launch_facet_sum(ctx->st, D.nint, 2 * D.m, D.yF, b, alpha, y);
+  } else {
+    int t = kt_begin(ctx, cls);
+    launch_apply(ctx->st, D.view(), x, y, alpha, b);
+    kt_end(ctx, cls, t, ctx->apply_bytes + (b ? D.ndof * 8.0 : 0.0));
   }
 }
 
 // Skeleton apply on the order-k level, timed as class 1.
 void apply_k(hdgmg_ctx* ctx, const double* x, double* y, double alpha, const double* b) {
-  int t = kt_begin(ctx, 1);
-  launch_apply(ctx->st, ctx->K.view(), x, y, alpha, b);
-  kt_end(ctx, 1, t, ctx->apply_bytes + (b ? ctx->K.ndof * 8.0 : 0.0));
+  level_apply(ctx, ctx->K, x, y, alpha, b, 1);
 }
 
 // Alg. 1 on lowest-order level l: u_l <- MG_h(l, g_l, u_l, m_l, q)
 void mg_h(hdgmg_ctx* ctx, int l, int m_l) {
   DevLevel& D = ctx->cr[l];
+  if (l <= ctx->Lc) {
+    int t = kt_begin(ctx, 4);
+    launch_coarse_cycle(ctx->st, ctx->coarse_desc, l, m_l, ctx->opts.vcycle_growth, ctx->opts.cycle,
+                        ctx->coarse_inv, ctx->n0, ctx->coarse_ns, ctx->coarse_lds);
+    kt_end(ctx, 4, t, 0.0);
+    return;
+  }
   if (l == 0) {
     launch_gemv_dense(ctx->st, ctx->n0, ctx->coarse_inv, D.g, D.u);
     return;
   }
   for (int s = 0; s < m_l; ++s) sweep(ctx, D, D.u, D.g, true, l);
-  launch_apply(ctx->st, D.view(), D.u, D.r, -1.0, D.g);
+  level_apply(ctx, D, D.u, D.r, -1.0, D.g, 2);
   DevTransfer& T = ctx->tr[l];
   DevLevel& C = ctx->cr[l - 1];
   launch_spmv(ctx->st, T.ncoarse, T.R_rp, T.R_ci, T.R_v, D.r, C.g, 0.0);
@@ -312,9 +418,51 @@ void mg_h(hdgmg_ctx* ctx, int l, int m_l) {
 
 // Alg. 2 with zero initial guess: z = MG_hp(r)
 void mg_hp_body(hdgmg_ctx* ctx, const double* r, double* z);
+bool timers_on(const hdgmg_ctx* ctx) {
+  for (const auto& T : ctx->timers)
+    if (T.on) return true;
+  return false;
+}
+
+void drop_graph(hdgmg_ctx* ctx) {
+  if (ctx->vc_exec) (void)hipGraphExecDestroy(ctx->vc_exec);
+  ctx->vc_exec = nullptr;
+  ctx->vc_r = nullptr;
+  ctx->vc_z = nullptr;
+}
+
+// The launch sequence of MG_hp depends only on the hierarchy and the
+// options, so it is captured once per (r, z) pair and replayed.  While live
+// kernel timers are on, the launches go eagerly (events bracket them).
 void mg_hp(hdgmg_ctx* ctx, const double* r, double* z) {
   int t = kt_begin(ctx, 3);
-  mg_hp_body(ctx, r, z);
+  if (!ctx->use_graph || timers_on(ctx)) {
+    mg_hp_body(ctx, r, z);
+  } else {
+    if (!ctx->vc_exec || ctx->vc_r != r || ctx->vc_z != z) {
+      drop_graph(ctx);
+      hipGraph_t g = nullptr;
+      bool ok = hipStreamBeginCapture(ctx->st, hipStreamCaptureModeThreadLocal) == hipSuccess;
+      if (ok) {
+        mg_hp_body(ctx, r, z);
+        ok = hipStreamEndCapture(ctx->st, &g) == hipSuccess && g;
+      }
+      if (ok) ok = hipGraphInstantiate(&ctx->vc_exec, g, nullptr, nullptr, 0) == hipSuccess;
+      if (g) (void)hipGraphDestroy(g);
+      if (!ok) {
+        // capture unavailable on this stream: run eagerly from now on
+        (void)hipGetLastError();
+        ctx->vc_exec = nullptr;
+        ctx->use_graph = false;
+        mg_hp_body(ctx, r, z);
+        kt_end(ctx, 3, t, ctx->vcycle_bytes);
+        return;
+      }
+      ctx->vc_r = r;
+      ctx->vc_z = z;
+    }
+    (void)hipGraphLaunch(ctx->vc_exec, ctx->st);
+  }
   kt_end(ctx, 3, t, ctx->vcycle_bytes);
 }
 void mg_hp_body(hdgmg_ctx* ctx, const double* r, double* z) {
@@ -428,6 +576,156 @@ hdgmg_status build_transfers(hdgmg_ctx* ctx) {
   return HDGMG_OK;
 }
 
+// Descriptors of the levels handled by the single-workgroup coarse kernel:
+// per patch row its padded residual row (from the assembled operator) and its
+// row of the patch inverse (host FP64 Cholesky), structure-of-arrays.
+hdgmg_status build_coarse(hdgmg_ctx* ctx) {
+  ctx->Lc = -1;
+  if (ctx->opts.coarse_dofs <= 0) return HDGMG_OK;
+  int Lc = -1, vec = 0, nsmax = 0;
+  for (int l = 0; l < ctx->J && l < COARSE_MAX_LEVELS; ++l) {
+    const Level& L = ctx->lv[l];
+    vec += 3 * 2 * L.nint;
+    if (2 * L.nint > ctx->opts.coarse_dofs || vec > COARSE_LDS_DOUBLES) break;
+    if (2 * L.max_patch_facets > 32) break;
+    nsmax = std::max(nsmax, 2 * L.max_patch_facets);
+    Lc = l;
+  }
+  if (Lc < 0) return HDGMG_OK;
+  std::vector<std::vector<double>> nu;
+  level_viscosities(ctx->lv, ctx->nu_fine, nu);
+  std::vector<CoarseLevel> desc(Lc + 1);
+  int off = COARSE_THREADS + 32;
+  for (int l = 0; l <= Lc; ++l) {
+    const Level& L = ctx->lv[l];
+    DevLevel& D = ctx->cr[l];
+    CoarseLevel& C = desc[l];
+    std::memset(&C, 0, sizeof(C));
+    const int n = 2 * L.nint;
+    C.n = n;
+    C.off_u = off;
+    C.off_g = off + n;
+    C.off_r = off + 2 * n;
+    off += 3 * n;
+    C.u_glob = D.u;
+    C.g_glob = D.g;
+    if (l == 0) continue;
+    std::vector<double> B;
+    host_cr_blocks(L, nu[l], ctx->beta, ctx->gamma, B);
+    CSR A;
+    assemble_csr(L, B, A);
+    // per-unknown padded rows
+    std::vector<int> rw_col((size_t)COARSE_NNZ * n, 0);
+    std::vector<double> rw_val((size_t)COARSE_NNZ * n, 0.0);
+    for (int i = 0; i < n; ++i) {
+      int nz = A.rp[i + 1] - A.rp[i];
+      if (nz > COARSE_NNZ) {
+        ctx->err = "lowest-order row with more than 10 entries";
+        return HDGMG_EMESH;
+      }
+      for (int k = 0; k < nz; ++k) {
+        rw_col[(size_t)k * n + i] = A.ci[A.rp[i] + k];
+        rw_val[(size_t)k * n + i] = A.v[A.rp[i] + k];
+      }
+    }
+    // items colour by colour, batches aligned to patches
+    int nsm = 2 * L.max_patch_facets;
+    std::vector<int> cb(1, 0), bitem(1, 0), idof, iloc;
+    std::vector<std::vector<double>> irow;  // inverse row per item
+    for (int c = 0; c < L.ncol; ++c) {
+      for (int p = L.colour_ptr[c]; p < L.colour_ptr[c + 1]; ++p) {
+        int f0 = L.patch_facet_ptr[p], nfp = L.patch_facet_ptr[p + 1] - f0;
+        int ns = 2 * nfp;
+        std::vector<int> dofs(ns);
+        for (int a = 0; a < nfp; ++a)
+          for (int comp = 0; comp < 2; ++comp) dofs[2 * a + comp] = 2 * L.patch_facets[f0 + a] + comp;
+        std::vector<double> Ass((size_t)ns * ns, 0.0), inv;
+        for (int i = 0; i < ns; ++i)
+          for (int q = A.rp[dofs[i]]; q < A.rp[dofs[i] + 1]; ++q)
+            for (int j = 0; j < ns; ++j)
+              if (A.ci[q] == dofs[j]) Ass[(size_t)i * ns + j] = A.v[q];
+        if (!invert_spd(Ass, ns, inv)) {
+          ctx->err = "singular patch block on a coarse level";
+          return HDGMG_ENONFINITE;
+        }
+        if ((int)idof.size() - bitem.back() + ns > COARSE_THREADS) bitem.push_back((int)idof.size());
+        for (int i = 0; i < ns; ++i) {
+          idof.push_back(dofs[i]);
+          iloc.push_back(i);
+          std::vector<double> row(nsm, 0.0);
+          for (int j = 0; j < ns; ++j) row[j] = inv[(size_t)i * ns + j];  // symmetric
+          irow.push_back(row);
+        }
+      }
+      if ((int)idof.size() > bitem.back()) bitem.push_back((int)idof.size());
+      cb.push_back((int)bitem.size() - 1);
+    }
+    const int nit = (int)idof.size();
+    if (n > 65535) {
+      ctx->err = "coarse level too large for 16-bit indices";
+      return HDGMG_EMESH;
+    }
+    std::vector<unsigned> it_key(nit), it_col((size_t)(COARSE_NNZ / 2) * nit);
+    std::vector<double> it_val((size_t)COARSE_NNZ * nit), it_ainv((size_t)std::max(nsm, 1) * nit);
+    for (int t = 0; t < nit; ++t) {
+      it_key[t] = (unsigned)idof[t] | ((unsigned)iloc[t] << 16);
+      for (int k = 0; k < COARSE_NNZ; ++k) it_val[(size_t)k * nit + t] = rw_val[(size_t)k * n + idof[t]];
+      for (int k = 0; k < COARSE_NNZ / 2; ++k)
+        it_col[(size_t)k * nit + t] = (unsigned)rw_col[(size_t)(2 * k) * n + idof[t]] |
+                                      ((unsigned)rw_col[(size_t)(2 * k + 1) * n + idof[t]] << 16);
+      for (int j = 0; j < nsm; ++j) it_ainv[(size_t)j * nit + t] = irow[t][j];
+    }
+    C.ncol = L.ncol;
+    C.nitems = nit;
+    C.ns_max = nsm;
+    C.nbatch = (int)bitem.size() - 1;
+    if (C.nbatch > COARSE_MAX_BATCH) {
+      ctx->err = "coarse level has too many batches";
+      return HDGMG_EMESH;
+    }
+    std::vector<int> bwd;
+    for (int c = L.ncol - 1; c >= 0; --c)
+      for (int bb = cb[c]; bb < cb[c + 1]; ++bb) bwd.push_back(bb);
+    int* ti;
+    double* td;
+    unsigned* tu;
+    TRY(upload(ctx, &ti, bwd));
+    C.bseq_bwd = ti;
+    TRY(upload(ctx, &tu, it_key));
+    C.it_key = tu;
+    TRY(upload(ctx, &ti, cb));
+    C.cb_ptr = ti;
+    TRY(upload(ctx, &ti, bitem));
+    C.bitem = ti;
+    TRY(upload(ctx, &tu, it_col));
+    C.it_col = tu;
+    TRY(upload(ctx, &td, it_val));
+    C.it_val = td;
+    TRY(upload(ctx, &td, it_ainv));
+    C.it_ainv = td;
+    TRY(upload(ctx, &ti, rw_col));
+    C.rw_col = ti;
+    TRY(upload(ctx, &td, rw_val));
+    C.rw_val = td;
+    const DevTransfer& T = ctx->tr[l];
+    C.R_rp = T.R_rp;
+    C.R_ci = T.R_ci;
+    C.R_v = T.R_v;
+    C.P_rp = T.P_rp;
+    C.P_ci = T.P_ci;
+    C.P_v = T.P_v;
+  }
+  std::vector<char> raw(sizeof(CoarseLevel) * desc.size());
+  std::memcpy(raw.data(), desc.data(), raw.size());
+  char* d;
+  TRY(upload(ctx, &d, raw));
+  ctx->coarse_desc = (CoarseLevel*)d;
+  ctx->coarse_lds = off;
+  ctx->coarse_ns = nsmax;
+  ctx->Lc = Lc;
+  return HDGMG_OK;
+}
+
 hdgmg_status batched(hdgmg_ctx* ctx, int nc, int k, int mode, const double* f, const double* lam,
                      const double* p0, double* out1, double* out2) {
   long per = element_ws_size(k);
@@ -465,6 +763,8 @@ void hdgmg_default_opts(hdgmg_opts* o) {
   o->max_it = 500;
   o->uzawa_max = 50;
   o->uzawa_tol = 1e-10;
+  o->coarse_dofs = 2048;
+  o->stream_dofs = 200000;
 }
 
 const char* hdgmg_last_error(const hdgmg_ctx* ctx) {
@@ -474,8 +774,10 @@ const char* hdgmg_last_error(const hdgmg_ctx* ctx) {
 void hdgmg_destroy(hdgmg_ctx* ctx) {
   if (!ctx) return;
   if (ctx->st) (void)hipStreamSynchronize(ctx->st);
+  drop_graph(ctx);
   for (auto& T : ctx->timers) kt_clear(T);
   for (void* p : ctx->allocs) (void)hipFree(p);
+  if (ctx->own) (void)hipStreamDestroy(ctx->own);
   delete ctx;
 }
 
@@ -520,6 +822,16 @@ hdgmg_status hdgmg_setup(const hdgmg_mesh* mesh, int k, double beta, const doubl
     return HDGMG_EINVAL;
   }
   ctx->st = (hipStream_t)stream;
+  if (!ctx->st) {
+    // a stream of our own (default priority); the legacy null stream cannot
+    // be captured into a graph
+    if (hipStreamCreate(&ctx->own) != hipSuccess) {
+      g_setup_error = "hipStreamCreate failed";
+      delete ctx;
+      return HDGMG_EHIP;
+    }
+    ctx->st = ctx->own;
+  }
   ctx->J = mesh->n_refine + 1;
   ctx->lv.resize(ctx->J);
   Level& L0 = ctx->lv[0];
@@ -622,15 +934,19 @@ hdgmg_status hdgmg_setup(const hdgmg_mesh* mesh, int k, double beta, const doubl
 hdgmg_status hdgmg_assemble(hdgmg_ctx* ctx) {
   if (!ctx) return HDGMG_EINVAL;
   ctx->assembled = false;
+  drop_graph(ctx);
   TRY(batched(ctx, ctx->K.nc, ctx->k, EL_CONDENSE, nullptr, nullptr, nullptr, nullptr, nullptr));
   TRY(patch_inverses(ctx, ctx->K));
+  TRY(pack_fast(ctx, ctx->K));
   TRY(build_transfers(ctx));
   for (int l = 0; l < ctx->J; ++l) {
     DevLevel& D = ctx->cr[l];
     launch_cr_blocks(ctx->st, D.X, D.cells, D.nc, D.nu, ctx->beta, ctx->gamma, D.S);
     HIPC(hipGetLastError());
     if (l > 0) TRY(patch_inverses(ctx, D));
+    if (l > 0) TRY(pack_fast(ctx, D));
   }
+  TRY(build_coarse(ctx));
   HIPC(hipStreamSynchronize(ctx->st));
   // algorithmic bytes of one MG_hp application (sum over its launches)
   {
@@ -774,7 +1090,7 @@ hdgmg_status hdgmg_solve(hdgmg_ctx* ctx, const double* f_qp, double* u_qp, doubl
 }
 
 hdgmg_status hdgmg_kernel_timer(hdgmg_ctx* ctx, int cls, int enable) {
-  if (!ctx || cls < 0 || cls > 3) return HDGMG_EINVAL;
+  if (!ctx || cls < 0 || cls > 4) return HDGMG_EINVAL;
   HIPC(hipStreamSynchronize(ctx->st));
   kt_clear(ctx->timers[cls]);
   ctx->timers[cls].on = enable != 0;
@@ -783,7 +1099,7 @@ hdgmg_status hdgmg_kernel_timer(hdgmg_ctx* ctx, int cls, int enable) {
 
 hdgmg_status hdgmg_kernel_timer_read(hdgmg_ctx* ctx, int cls, double* total_ms, int64_t* launches,
                                      double* bytes) {
-  if (!ctx || cls < 0 || cls > 3) return HDGMG_EINVAL;
+  if (!ctx || cls < 0 || cls > 4) return HDGMG_EINVAL;
   HIPC(hipStreamSynchronize(ctx->st));
   auto& T = ctx->timers[cls];
   double tot = 0.0;

@@ -36,6 +36,7 @@ _ORACLES = {}
 
 
 def oracle_setup(key, coords, cells, n_refine, k, nu, beta, gamma, **kw):
+    kw = {a: b for a, b in kw.items() if a not in ("coarse_dofs", "stream_dofs")}  # layout only
     if key not in _ORACLES:
         _ORACLES[key] = solver.Setup(coords, cells, n_refine, k, nu, beta, gamma, **kw)
     return _ORACLES[key]
@@ -76,6 +77,18 @@ CASES = {
     "tiny_k1": (lambda: synth.kuhn_square(1), 1, 1, 1.0, 1.0, 1e2, {}),
     "wcycle_k1": (lambda: synth.kuhn_square(2), 2, 1, 1.0, 1.0, 1e2, dict(q=2, growth=1)),
     "m2_k2": (lambda: synth.kuhn_square(2), 2, 2, 1.0, 1e3, 1e2, dict(m_p=2, m_h=2)),
+    # every lowest-order level launched level by level
+    "k1_per_level": (lambda: synth.kuhn_square(4), 2, 1, 1.0, 1.0, 1e2, dict(coarse_dofs=0)),
+    # levels 0-1 in the single-workgroup kernel, level 2 launched
+    "k2_split": (lambda: synth.kuhn_square(4), 2, 2, 1.0, 1.0, 1e2, dict(coarse_dofs=400)),
+    "wcycle_split": (lambda: synth.kuhn_square(2), 3, 1, 1.0, 1.0, 1e2,
+                     dict(q=2, growth=1, coarse_dofs=400)),
+    # streaming cell-apply / patch-relax kernels on every level
+    "k0_stream": (lambda: synth.kuhn_square(4), 2, 0, 1.0, 1.0, 1e2, dict(stream_dofs=0, coarse_dofs=0)),
+    "k1_stream": (lambda: synth.kuhn_square(4), 1, 1, 1.0, 1.0, 1e2, dict(stream_dofs=0)),
+    "k2_stream": (lambda: synth.kuhn_square(4), 2, 2, 1.0, 1.0, 1e2, dict(stream_dofs=0, coarse_dofs=400)),
+    "k3_stream": (lambda: synth.kuhn_square(4), 1, 3, 1.0, 0.0, 1e4, dict(stream_dofs=0)),
+    "k4_stream": (lambda: jittered_square(4, 5), 1, 4, 0.7, 2.0, 1e2, dict(stream_dofs=0)),
 }
 
 
@@ -135,7 +148,8 @@ def test_inner_solve(name):
     assert np.linalg.norm(x - x_o) <= 1e-9 * np.linalg.norm(x_o)
 
 
-@pytest.mark.parametrize("name", ["k0", "k2", "beta0_gamma1e4", "jittered_k2", "one_level_k2"])
+@pytest.mark.parametrize("name", ["k0", "k2", "beta0_gamma1e4", "jittered_k2", "one_level_k2",
+                                  "k2_split", "k2_stream", "k4_stream"])
 def test_full_solve(name):
     c, t, nref, k, nu, beta, gamma, kw = case(name)
     _note(f"[full solve] {name}")
@@ -202,3 +216,20 @@ def test_error_paths():
     f = synth.source_uniform(0, 1, s2.n_cells, s2.n_q)[0]
     _, _, _, _, st = s2.solve(dev(f))
     assert st == 1
+
+
+def test_preconditioner_graph_replays():
+    """MG_hp is captured as a HIP graph per (r, z) pair and replayed: several
+    replays with eager work in between must each match the oracle."""
+    c, t, nref, k, nu, beta, gamma, kw = case("k2_split")
+    _note("[graph replay] k2_split")
+    O = oracle_setup("k2_split", c, t, nref, k, nu, beta, gamma, **kw)
+    G = gpu_solver(c, t, nref, k, nu, beta, gamma, **kw)
+    r_dev = dev(np.zeros(G.n_skel))
+    z_dev = dev(np.zeros(G.n_skel))
+    for rep in range(4):
+        r = synth.uniform_pm1(40 + rep, 0, (G.n_skel,))
+        r_dev.copy_(dev(r))
+        G.apply(r_dev)                      # eager work between replays
+        G.precondition(r_dev, out=z_dev)
+        assert rel(host(z_dev), O.prec(r)) < 1e-10, rep
