@@ -94,11 +94,14 @@ typedef struct {
   int stream_dofs;         /* levels with at least this many unknowns (and
                               vertex patches of at most 6 facets) use the
                               streaming cell-apply / patch-relax kernels   */
+  int vcycle_precision;    /* storage of every operator the preconditioner
+                              reads: 0 FP64, 1 FP32 (vectors, accumulation
+                              and the outer Krylov solver stay FP64)       */
 } hdgmg_opts;
 
 /* Defaults: m_p = m_h = 1, V-cycle, growth 2, rtol 1e-8, atol 1e-10,
  * max_it 500, uzawa_max 50, uzawa_tol 1e-10, coarse_dofs 2048,
- * stream_dofs 200000. */
+ * stream_dofs 200000, vcycle_precision 0. */
 void hdgmg_default_opts(hdgmg_opts* opts);
 
 #define HDGMG_MAX_UZAWA 64

@@ -24,30 +24,32 @@ namespace {
 constexpr int CT = COARSE_THREADS;
 
 // The record of one patch row: its unknown and row, residual row, inverse row.
-template <int NS>
+template <int NS, typename TS>
 struct Rec {
   unsigned key;
   unsigned col[COARSE_NNZ / 2];
-  double val[COARSE_NNZ];
-  double ai[NS];
+  TS val[COARSE_NNZ];
+  TS ai[NS];
 };
 
-template <int NS>
-__device__ inline void load_rec(const CoarseLevel& L, int t, Rec<NS>& r) {
+template <int NS, typename TS>
+__device__ inline void load_rec(const CoarseLevel& L, int t, Rec<NS, TS>& r) {
   const int nit = L.nitems;
+  const TS* val = (const TS*)L.it_val;
+  const TS* ainv = (const TS*)L.it_ainv;
   r.key = L.it_key[t];
 #pragma unroll
   for (int k = 0; k < COARSE_NNZ / 2; ++k) r.col[k] = L.it_col[k * nit + t];
 #pragma unroll
-  for (int k = 0; k < COARSE_NNZ; ++k) r.val[k] = L.it_val[k * nit + t];
+  for (int k = 0; k < COARSE_NNZ; ++k) r.val[k] = val[k * nit + t];
 #pragma unroll
-  for (int j = 0; j < NS; ++j) r.ai[j] = j < L.ns_max ? L.it_ainv[j * nit + t] : 0.0;
+  for (int j = 0; j < NS; ++j) r.ai[j] = j < L.ns_max ? ainv[j * nit + t] : (TS)0;
 }
 
 // `sweeps` block Gauss-Seidel sweeps over the colours (forward or reversed),
 // as a flat list of batches; the next batch's records are loaded while the
 // current batch computes (they do not depend on u).
-template <int NS>
+template <int NS, typename TS>
 __device__ void smooth(const CoarseLevel& L, int sweeps, bool forward, double* __restrict__ res,
                        double* __restrict__ u, const double* __restrict__ g) {
   const int tid = threadIdx.x;
@@ -55,26 +57,26 @@ __device__ void smooth(const CoarseLevel& L, int sweeps, bool forward, double* _
   const int steps = sweeps * nb;
   if (steps == 0) return;
   auto batch_of = [&](int s) { return forward ? s % nb : L.bseq_bwd[s % nb]; };
-  Rec<NS> cur, nxt;
+  Rec<NS, TS> cur, nxt;
   int b = batch_of(0);
   int t = L.bitem[b] + tid;
   bool on = t < L.bitem[b + 1];
-  if (on) load_rec<NS>(L, t, cur);
+  if (on) load_rec<NS, TS>(L, t, cur);
   for (int s = 0; s < steps; ++s) {
     bool onn = false;
     if (s + 1 < steps) {
       const int bn = batch_of(s + 1);
       const int tn = L.bitem[bn] + tid;
       onn = tn < L.bitem[bn + 1];
-      if (onn) load_rec<NS>(L, tn, nxt);
+      if (onn) load_rec<NS, TS>(L, tn, nxt);
     }
     const int dof = cur.key & 0xffff, loc = cur.key >> 16;
     if (on) {
       double r = g[dof];
 #pragma unroll
       for (int k = 0; k < COARSE_NNZ / 2; ++k) {
-        r -= cur.val[2 * k] * u[cur.col[k] & 0xffff];
-        r -= cur.val[2 * k + 1] * u[cur.col[k] >> 16];
+        r -= (double)cur.val[2 * k] * u[cur.col[k] & 0xffff];
+        r -= (double)cur.val[2 * k + 1] * u[cur.col[k] >> 16];
       }
       res[tid] = r;
     }
@@ -83,7 +85,7 @@ __device__ void smooth(const CoarseLevel& L, int sweeps, bool forward, double* _
       const int base = tid - loc;
       double d = 0.0;
 #pragma unroll
-      for (int j = 0; j < NS; ++j) d += cur.ai[j] * res[base + j];
+      for (int j = 0; j < NS; ++j) d += (double)cur.ai[j] * res[base + j];
       u[dof] += d;
     }
     __syncthreads();
@@ -92,10 +94,9 @@ __device__ void smooth(const CoarseLevel& L, int sweeps, bool forward, double* _
   }
 }
 
-template <int NS>
+template <int NS, typename TS>
 __global__ void __launch_bounds__(CT) k_coarse_cycle(const CoarseLevel* __restrict__ Lg, int top, int m_top,
-                                                     int growth, int q, const double* __restrict__ inv0,
-                                                     int n0) {
+                                                     int growth, int q, const TS* __restrict__ inv0, int n0) {
   extern __shared__ double smem[];
   __shared__ CoarseLevel Ls[COARSE_MAX_LEVELS];
   const int tid = threadIdx.x;
@@ -126,7 +127,7 @@ __global__ void __launch_bounds__(CT) k_coarse_cycle(const CoarseLevel* __restri
       for (int i = tid; i < n0; i += CT) {
         double s = 0.0;
 #pragma unroll 8
-        for (int j = 0; j < n0; ++j) s += inv0[(long)j * n0 + i] * g0[j];
+        for (int j = 0; j < n0; ++j) s += (double)inv0[(long)j * n0 + i] * g0[j];
         u0[i] = s;
       }
       __syncthreads();
@@ -142,17 +143,19 @@ __global__ void __launch_bounds__(CT) k_coarse_cycle(const CoarseLevel* __restri
     double* ub = smem + B.off_u;
     double* gb = smem + B.off_g;
     if (state[l] == 0) {
-      smooth<NS>(L, mlev[l], true, res, u, g);
+      smooth<NS, TS>(L, mlev[l], true, res, u, g);
+      const TS* rwv = (const TS*)L.rw_val;
+      const TS* Rv = (const TS*)L.R_v;
       for (int i = tid; i < L.n; i += CT) {
         double s = g[i];
 #pragma unroll
-        for (int k = 0; k < COARSE_NNZ; ++k) s -= L.rw_val[k * L.n + i] * u[L.rw_col[k * L.n + i]];
+        for (int k = 0; k < COARSE_NNZ; ++k) s -= (double)rwv[k * L.n + i] * u[L.rw_col[k * L.n + i]];
         r[i] = s;
       }
       __syncthreads();
       for (int i = tid; i < B.n; i += CT) {
         double s = 0.0;
-        for (int k = L.R_rp[i]; k < L.R_rp[i + 1]; ++k) s += L.R_v[k] * r[L.R_ci[k]];
+        for (int k = L.R_rp[i]; k < L.R_rp[i + 1]; ++k) s += (double)Rv[k] * r[L.R_ci[k]];
         gb[i] = s;
         ub[i] = 0.0;
       }
@@ -168,13 +171,14 @@ __global__ void __launch_bounds__(CT) k_coarse_cycle(const CoarseLevel* __restri
       --l;
       continue;
     }
+    const TS* Pv = (const TS*)L.P_v;
     for (int i = tid; i < L.n; i += CT) {
       double s = 0.0;
-      for (int k = L.P_rp[i]; k < L.P_rp[i + 1]; ++k) s += L.P_v[k] * ub[L.P_ci[k]];
+      for (int k = L.P_rp[i]; k < L.P_rp[i + 1]; ++k) s += (double)Pv[k] * ub[L.P_ci[k]];
       u[i] += s;
     }
     __syncthreads();
-    smooth<NS>(L, mlev[l], false, res, u, g);
+    smooth<NS, TS>(L, mlev[l], false, res, u, g);
     if (l == top) break;
     ++l;
   }
@@ -187,15 +191,24 @@ __global__ void __launch_bounds__(CT) k_coarse_cycle(const CoarseLevel* __restri
 
 }  // namespace
 
-void launch_coarse_cycle(hipStream_t st, const CoarseLevel* Ls, int top, int m_top, int growth, int q,
-                         const double* inv0, int n0, int ns_max, int lds_doubles) {
-  size_t shm = sizeof(double) * (size_t)lds_doubles;
+template <typename TS>
+void coarse_t(hipStream_t st, const CoarseLevel* Ls, int top, int m_top, int growth, int q, const TS* inv0,
+              int n0, int ns_max, size_t shm) {
   if (ns_max <= 12)
-    hipLaunchKernelGGL(k_coarse_cycle<12>, dim3(1), dim3(CT), shm, st, Ls, top, m_top, growth, q, inv0, n0);
+    hipLaunchKernelGGL((k_coarse_cycle<12, TS>), dim3(1), dim3(CT), shm, st, Ls, top, m_top, growth, q, inv0, n0);
   else if (ns_max <= 16)
-    hipLaunchKernelGGL(k_coarse_cycle<16>, dim3(1), dim3(CT), shm, st, Ls, top, m_top, growth, q, inv0, n0);
+    hipLaunchKernelGGL((k_coarse_cycle<16, TS>), dim3(1), dim3(CT), shm, st, Ls, top, m_top, growth, q, inv0, n0);
   else
-    hipLaunchKernelGGL(k_coarse_cycle<32>, dim3(1), dim3(CT), shm, st, Ls, top, m_top, growth, q, inv0, n0);
+    hipLaunchKernelGGL((k_coarse_cycle<32, TS>), dim3(1), dim3(CT), shm, st, Ls, top, m_top, growth, q, inv0, n0);
+}
+
+void launch_coarse_cycle(hipStream_t st, const CoarseLevel* Ls, int top, int m_top, int growth, int q,
+                         const void* inv0, int n0, int ns_max, int lds_doubles, int f32) {
+  size_t shm = sizeof(double) * (size_t)lds_doubles;
+  if (f32)
+    coarse_t<float>(st, Ls, top, m_top, growth, q, (const float*)inv0, n0, ns_max, shm);
+  else
+    coarse_t<double>(st, Ls, top, m_top, growth, q, (const double*)inv0, n0, ns_max, shm);
 }
 
 }  // namespace hdgmg

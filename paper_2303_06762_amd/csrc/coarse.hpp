@@ -17,6 +17,8 @@ constexpr int COARSE_MAX_BATCH = 64;
 
 // One lowest-order level as seen by the coarse kernel (device pointers;
 // per-item arrays are structure-of-arrays: entry e of item t at [e*nitems+t]).
+// Operator values (it_val, it_ainv, rw_val, R_v, P_v) are stored in the
+// storage type the kernel is launched with (double or float).
 struct CoarseLevel {
   int n;                      // unknowns (2 per interior facet)
   int ncol, nitems, ns_max;   // colours, patch rows, largest patch
@@ -29,16 +31,16 @@ struct CoarseLevel {
   const unsigned* it_key;     // [nitems] unknown | (row inside its patch) << 16
   const unsigned* it_col;     // [COARSE_NNZ/2][nitems] residual row columns,
                               // two 16-bit indices per word
-  const double* it_val;       // [COARSE_NNZ][nitems] residual row: values
-  const double* it_ainv;      // [ns_max][nitems] row of the patch inverse
+  const void* it_val;         // [COARSE_NNZ][nitems] residual row: values
+  const void* it_ainv;        // [ns_max][nitems] row of the patch inverse
   const int* rw_col;          // [COARSE_NNZ][n] rows of A for the residual
-  const double* rw_val;
+  const void* rw_val;
   const int* R_rp;            // restriction to level l-1 (CSR, its unknowns)
   const int* R_ci;
-  const double* R_v;
+  const void* R_v;
   const int* P_rp;            // prolongation from level l-1 (CSR, these unknowns)
   const int* P_ci;
-  const double* P_v;
+  const void* P_v;
   double* u_glob;             // level vectors in HBM (used at the top level)
   double* g_glob;
 };
@@ -47,7 +49,8 @@ struct CoarseLevel {
 // levels 0..top (top <= the levels described by Ls); level 0 is solved with
 // the dense column-major inverse inv0 (n0 x n0).  lds_doubles: the dynamic
 // LDS the descriptors' offsets need.
+// f32 != 0: operator values (and inv0) are float, else double.
 void launch_coarse_cycle(hipStream_t st, const CoarseLevel* Ls, int top, int m_top, int growth, int q,
-                         const double* inv0, int n0, int ns_max, int lds_doubles);
+                         const void* inv0, int n0, int ns_max, int lds_doubles, int f32);
 
 }  // namespace hdgmg

@@ -203,10 +203,13 @@ void patch_relax_t(hipStream_t st, int m2, int np, const int* pf, const TS* Pp, 
 
 }  // namespace
 
-void launch_cell_apply(hipStream_t st, int m2, int nc, const double* Sp, const int* cdof, const double* x,
+template <typename TS>
+void launch_cell_apply(hipStream_t st, int m2, int nc, const TS* Sp, const int* cdof, const double* x,
                        double* yF) {
-  if (nc > 0) cell_apply_t<double>(st, m2, nc, Sp, cdof, x, yF);
+  if (nc > 0) cell_apply_t<TS>(st, m2, nc, Sp, cdof, x, yF);
 }
+template void launch_cell_apply<double>(hipStream_t, int, int, const double*, const int*, const double*, double*);
+template void launch_cell_apply<float>(hipStream_t, int, int, const float*, const int*, const double*, double*);
 
 void launch_facet_sum(hipStream_t st, int nint, int m2, const double* yF, const double* b, double alpha,
                       double* y) {
@@ -214,10 +217,15 @@ void launch_facet_sum(hipStream_t st, int nint, int m2, const double* yF, const 
   if (n > 0) hipLaunchKernelGGL(k_facet_sum, dim3(nblk(n)), dim3(256), 0, st, n, m2, yF, b, alpha, y);
 }
 
-void launch_patch_relax(hipStream_t st, int m2, int np, const int* pf, const double* Pp, const double* b,
+template <typename TS>
+void launch_patch_relax(hipStream_t st, int m2, int np, const int* pf, const TS* Pp, const double* b,
                         const double* yF, double* x) {
-  if (np > 0) patch_relax_t<double>(st, m2, np, pf, Pp, b, yF, x);
+  if (np > 0) patch_relax_t<TS>(st, m2, np, pf, Pp, b, yF, x);
 }
+template void launch_patch_relax<double>(hipStream_t, int, int, const int*, const double*, const double*,
+                                         const double*, double*);
+template void launch_patch_relax<float>(hipStream_t, int, int, const int*, const float*, const double*,
+                                        const double*, double*);
 
 void launch_pack_cells(hipStream_t st, int nc, int nK, const double* S, double* Sp) {
   if (nc <= 0) return;

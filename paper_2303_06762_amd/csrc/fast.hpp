@@ -16,13 +16,15 @@ inline long fast_cell_words(int nK) { return nK <= 18 ? (long)nK * (nK + 1) / 2 
 
 // y_F[(2F+side)*m2 + c] = rows of S_K x_K for every cell K (m2 = 2 modes
 // per facet component x 2 components).
-void launch_cell_apply(hipStream_t st, int m2, int nc, const double* Sp, const int* cdof, const double* x,
+template <typename TS>
+void launch_cell_apply(hipStream_t st, int m2, int nc, const TS* Sp, const int* cdof, const double* x,
                        double* yF);
 // y = b + alpha * (y_F[side 0] + y_F[side 1]) (b may be null)
 void launch_facet_sum(hipStream_t st, int nint, int m2, const double* yF, const double* b, double alpha,
                       double* y);
 // x_s += A_ss^-1 (b - y)_s for the np patches of one colour
-void launch_patch_relax(hipStream_t st, int m2, int np, const int* pf, const double* Pp, const double* b,
+template <typename TS>
+void launch_patch_relax(hipStream_t st, int m2, int np, const int* pf, const TS* Pp, const double* b,
                         const double* yF, double* x);
 void launch_pack_cells(hipStream_t st, int nc, int nK, const double* S, double* Sp);
 void launch_pack_patches(hipStream_t st, int np, int gp0, int m2, const int* pf_ptr, const long* pinv_off,

@@ -147,25 +147,27 @@ __global__ void k_patch_inverse(LevelView L, const int* __restrict__ pc_ptr, con
 }
 
 // Row (facet fi, local row rr) of A x: sum over the two cells of fi.
-__device__ inline double row_dot(const LevelView& L, int fi, int rr, const double* __restrict__ x) {
+template <typename TS>
+__device__ inline double row_dot(const LevelViewT<TS>& L, int fi, int rr, const double* __restrict__ x) {
   const int m2 = 2 * L.m;
   double acc = 0.0;
   for (int s = 0; s < 2; ++s) {
     int K = L.fcell[2 * fi + s];
     int i = L.floc[2 * fi + s];
-    const double* row = L.S + ((long)K * L.nK + i * m2 + rr) * L.nK;
+    const TS* row = L.S + ((long)K * L.nK + i * m2 + rr) * L.nK;
     for (int i2 = 0; i2 < 3; ++i2) {
       int d = L.cell_dofs[3 * K + i2];
       if (d < 0) continue;
       const double* xd = x + (long)d * m2;
-      const double* rw = row + i2 * m2;
-      for (int c = 0; c < m2; ++c) acc += rw[c] * xd[c];
+      const TS* rw = row + i2 * m2;
+      for (int c = 0; c < m2; ++c) acc += (double)rw[c] * xd[c];
     }
   }
   return acc;
 }
 
-__global__ void k_apply(LevelView L, const double* __restrict__ x, double* __restrict__ y,
+template <typename TS>
+__global__ void k_apply(LevelViewT<TS> L, const double* __restrict__ x, double* __restrict__ y,
                         double alpha, const double* __restrict__ b) {
   long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const int m2 = 2 * L.m;
@@ -191,7 +193,8 @@ __global__ void k_gather_cells(LevelView L, const double* __restrict__ vK, doubl
 // Block Gauss-Seidel step on the patches [p0, p1) of one colour: one
 // wavefront per patch.  x_s += (A_ss)^-1 (b - A x)_s.  Patches of a colour
 // share no cell, so their reads of x never see a same-phase write.
-__global__ void __launch_bounds__(64) k_gs(LevelView L, int p0, double* x, const double* __restrict__ b) {
+template <typename TS>
+__global__ void __launch_bounds__(64) k_gs(LevelViewT<TS> L, int p0, double* x, const double* __restrict__ b) {
   __shared__ double res[GS_MAX_NS];
   const int p = p0 + blockIdx.x;
   const int m2 = 2 * L.m;
@@ -203,12 +206,12 @@ __global__ void __launch_bounds__(64) k_gs(LevelView L, int p0, double* x, const
     res[t] = b[d] - row_dot(L, fi, rr, x);
   }
   __syncthreads();
-  const double* Ai = L.pinv + L.pinv_off[p];
+  const TS* Ai = L.pinv + L.pinv_off[p];
   double dlt[GS_MAX_NS / 64];
   int cnt = 0;
   for (int t = threadIdx.x; t < ns; t += blockDim.x, ++cnt) {
     double s = 0.0;
-    for (int j = 0; j < ns; ++j) s += Ai[(long)j * ns + t] * res[j];
+    for (int j = 0; j < ns; ++j) s += (double)Ai[(long)j * ns + t] * res[j];
     dlt[cnt] = s;
   }
   __syncthreads();
@@ -241,13 +244,31 @@ __global__ void k_spmv(int nrows, const int* __restrict__ rp, const int* __restr
   y[r] = beta_y == 0.0 ? s : beta_y * y[r] + s;
 }
 
-__global__ void k_gemv_dense(int n, const double* __restrict__ A, const double* __restrict__ x,
+// ELL (padded, column-major) sparse matrix-vector product: entry k of row r
+// at [k * n + r], padding has value 0 and column 0.
+template <typename TS>
+__global__ void k_ell_spmv(int n, int w, const int* __restrict__ ci, const TS* __restrict__ v,
+                           const double* __restrict__ x, double* y, double beta_y) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  double s = 0.0;
+  for (int k = 0; k < w; ++k) s += (double)v[(long)k * n + r] * x[ci[(long)k * n + r]];
+  y[r] = beta_y == 0.0 ? s : beta_y * y[r] + s;
+}
+
+template <typename TS>
+__global__ void k_gemv_dense(int n, const TS* __restrict__ A, const double* __restrict__ x,
                              double* __restrict__ y) {
   int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
   double s = 0.0;
-  for (int c = 0; c < n; ++c) s += A[(long)c * n + r] * x[c];  // column-major
+  for (int c = 0; c < n; ++c) s += (double)A[(long)c * n + r] * x[c];  // column-major
   y[r] = s;
+}
+
+__global__ void k_to_f32(long n, const double* __restrict__ in, float* __restrict__ out) {
+  long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) out[t] = (float)in[t];
 }
 
 __global__ void k_fill(long n, double v, double* x) {
@@ -403,20 +424,31 @@ void launch_patch_inverse(hipStream_t st, LevelView L, const int* pc_ptr, const 
   hipLaunchKernelGGL(k_patch_inverse, dim3(nblk(npatch, 64)), dim3(64), 0, st, L, pc_ptr, pc, npatch,
                      max_ns, ws, pinv, status);
 }
-void launch_apply(hipStream_t st, LevelView L, const double* x, double* y, double alpha, const double* b) {
+template <typename TS>
+void launch_apply(hipStream_t st, LevelViewT<TS> L, const double* x, double* y, double alpha, const double* b) {
   long n = (long)L.nint * 2 * L.m;
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_apply, dim3(nblk(n)), dim3(TPB), 0, st, L, x, y, alpha, b);
+  hipLaunchKernelGGL(k_apply<TS>, dim3(nblk(n)), dim3(TPB), 0, st, L, x, y, alpha, b);
+}
+template void launch_apply<double>(hipStream_t, LevelViewT<double>, const double*, double*, double,
+                                   const double*);
+template void launch_apply<float>(hipStream_t, LevelViewT<float>, const double*, double*, double,
+                                  const double*);
+void launch_to_f32(hipStream_t st, long n, const double* in, float* out) {
+  if (n > 0) hipLaunchKernelGGL(k_to_f32, dim3(nblk(n)), dim3(TPB), 0, st, n, in, out);
 }
 void launch_gather_cells(hipStream_t st, LevelView L, const double* vK, double* y) {
   long n = (long)L.nint * 2 * L.m;
   if (n <= 0) return;
   hipLaunchKernelGGL(k_gather_cells, dim3(nblk(n)), dim3(TPB), 0, st, L, vK, y);
 }
-void launch_gs(hipStream_t st, LevelView L, int p0, int p1, double* x, const double* b) {
+template <typename TS>
+void launch_gs(hipStream_t st, LevelViewT<TS> L, int p0, int p1, double* x, const double* b) {
   if (p1 <= p0) return;
-  hipLaunchKernelGGL(k_gs, dim3(p1 - p0), dim3(64), 0, st, L, p0, x, b);
+  hipLaunchKernelGGL(k_gs<TS>, dim3(p1 - p0), dim3(64), 0, st, L, p0, x, b);
 }
+template void launch_gs<double>(hipStream_t, LevelViewT<double>, int, int, double*, const double*);
+template void launch_gs<float>(hipStream_t, LevelViewT<float>, int, int, double*, const double*);
 void launch_mode0_extract(hipStream_t st, int nint, int m, const double* r, double* g0) {
   if (nint <= 0) return;
   hipLaunchKernelGGL(k_mode0_extract, dim3(nblk(2L * nint)), dim3(TPB), 0, st, nint, m, r, g0);
@@ -430,10 +462,23 @@ void launch_spmv(hipStream_t st, int nrows, const int* rp, const int* ci, const 
   if (nrows <= 0) return;
   hipLaunchKernelGGL(k_spmv, dim3(nblk(nrows)), dim3(TPB), 0, st, nrows, rp, ci, v, x, y, beta_y);
 }
-void launch_gemv_dense(hipStream_t st, int n, const double* A, const double* x, double* y) {
+template <typename TS>
+void launch_ell_spmv(hipStream_t st, int n, int w, const int* ci, const TS* v, const double* x, double* y,
+                     double beta_y) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_gemv_dense, dim3(nblk(n)), dim3(TPB), 0, st, n, A, x, y);
+  hipLaunchKernelGGL(k_ell_spmv<TS>, dim3(nblk(n)), dim3(TPB), 0, st, n, w, ci, v, x, y, beta_y);
 }
+template void launch_ell_spmv<double>(hipStream_t, int, int, const int*, const double*, const double*, double*,
+                                      double);
+template void launch_ell_spmv<float>(hipStream_t, int, int, const int*, const float*, const double*, double*,
+                                     double);
+template <typename TS>
+void launch_gemv_dense(hipStream_t st, int n, const TS* A, const double* x, double* y) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_gemv_dense<TS>, dim3(nblk(n)), dim3(TPB), 0, st, n, A, x, y);
+}
+template void launch_gemv_dense<double>(hipStream_t, int, const double*, const double*, double*);
+template void launch_gemv_dense<float>(hipStream_t, int, const float*, const double*, double*);
 void launch_fill(hipStream_t st, long n, double v, double* x) {
   if (n > 0) hipLaunchKernelGGL(k_fill, dim3(nblk(n)), dim3(TPB), 0, st, n, v, x);
 }

@@ -9,18 +9,20 @@
 
 namespace hdgmg {
 
-// Level data on the device.
-struct LevelView {
+// Level data on the device; TS is the storage type of the operators.
+template <typename TS>
+struct LevelViewT {
   int nc, nint, m, nK;
   const int* cell_dofs;   // [nc][3] interior facet id or -1
   const int* fcell;       // [nint][2] the two cells of each interior facet
   const int* floc;        // [nint][2] local facet index in those cells
-  const double* S;        // [nc][nK][nK] cell blocks of A^eps (symmetric)
+  const TS* S;            // [nc][nK][nK] cell blocks of A^eps (symmetric)
   const int* pf_ptr;      // patch -> facets CSR
   const int* pf;
   const long* pinv_off;   // patch -> offset of its inverse (column-major)
-  const double* pinv;
+  const TS* pinv;
 };
+using LevelView = LevelViewT<double>;
 
 // Scalars of the flexible-CG recurrence kept on the device.
 enum { SC_ZR = 0, SC_PQ, SC_RR, SC_ZRN, SC_ZRO, SC_BB, SC_DP, SC_PP, SC_N };
@@ -40,16 +42,24 @@ void launch_cr_blocks(hipStream_t st, const double* X, const int* cells, int nc,
 void launch_patch_inverse(hipStream_t st, LevelView L, const int* pc_ptr, const int* pc,
                           int npatch, int max_ns, double* ws, double* pinv, int* status);
 // y = alpha * A x + (b ? b : 0)
-void launch_apply(hipStream_t st, LevelView L, const double* x, double* y, double alpha,
+template <typename TS>
+void launch_apply(hipStream_t st, LevelViewT<TS> L, const double* x, double* y, double alpha,
                   const double* b);
 // y[d] = sum over the two cells of F of per-cell vector entries (gather)
 void launch_gather_cells(hipStream_t st, LevelView L, const double* vK, double* y);
-void launch_gs(hipStream_t st, LevelView L, int p0, int p1, double* x, const double* b);
+template <typename TS>
+void launch_gs(hipStream_t st, LevelViewT<TS> L, int p0, int p1, double* x, const double* b);
+// out[i] = (float) in[i]
+void launch_to_f32(hipStream_t st, long n, const double* in, float* out);
 void launch_mode0_extract(hipStream_t st, int nint, int m, const double* r, double* g0);
 void launch_mode0_add(hipStream_t st, int nint, int m, const double* u0, double* x);
 void launch_spmv(hipStream_t st, int nrows, const int* rp, const int* ci, const double* v,
                  const double* x, double* y, double beta_y);
-void launch_gemv_dense(hipStream_t st, int n, const double* A, const double* x, double* y);
+template <typename TS>
+void launch_ell_spmv(hipStream_t st, int n, int w, const int* ci, const TS* v, const double* x, double* y,
+                     double beta_y);
+template <typename TS>
+void launch_gemv_dense(hipStream_t st, int n, const TS* A, const double* x, double* y);
 void launch_fill(hipStream_t st, long n, double v, double* x);
 void launch_copy(hipStream_t st, long n, const double* x, double* y);
 // partial sums of x.y into part[nblocks]; finalize part into sc[slot]

@@ -61,6 +61,29 @@ struct DevLevel {
   std::vector<double*> Ppc;  // per colour packed SoA patch inverses
   double bytes_cell = 0.0, bytes_sum = 0.0;
   std::vector<double> bytes_relax;
+  // storage the preconditioner reads: FP64 arrays above, or FP32 copies
+  bool f32 = false;
+  float *S32 = nullptr, *pinv32 = nullptr, *Sp32 = nullptr;
+  std::vector<float*> Pp32;
+  double bytes_cell_vc = 0.0;
+  std::vector<double> bytes_relax_vc;
+  template <typename TS>
+  LevelViewT<TS> view_t() const {
+    LevelViewT<TS> v;
+    v.nc = nc;
+    v.nint = nint;
+    v.m = m;
+    v.nK = nK;
+    v.cell_dofs = cell_dofs;
+    v.fcell = fcell;
+    v.floc = floc;
+    v.S = (const TS*)(f32 ? (const void*)S32 : (const void*)S);
+    v.pf_ptr = pf_ptr;
+    v.pf = pf;
+    v.pinv_off = pinv_off;
+    v.pinv = (const TS*)(f32 ? (const void*)pinv32 : (const void*)pinv);
+    return v;
+  }
   LevelView view() const {
     LevelView v;
     v.nc = nc;
@@ -86,7 +109,25 @@ struct DevTransfer {
   double* P_v = nullptr;
   int *R_rp = nullptr, *R_ci = nullptr;
   double* R_v = nullptr;
+  // the same operators in ELL form for the per-level launches
+  int Pw = 0, Rw = 0;
+  int *Pe_ci = nullptr, *Re_ci = nullptr;
+  double *Pe_v = nullptr, *Re_v = nullptr;
+  float *Pe_v32 = nullptr, *Re_v32 = nullptr, *P_v32 = nullptr, *R_v32 = nullptr;
 };
+
+// CSR -> ELL (column-major, zero padding).
+void to_ell(const CSR& A, int& w, std::vector<int>& ci, std::vector<double>& v) {
+  w = 0;
+  for (int r = 0; r < A.n; ++r) w = std::max(w, A.rp[r + 1] - A.rp[r]);
+  ci.assign((size_t)w * A.n, 0);
+  v.assign((size_t)w * A.n, 0.0);
+  for (int r = 0; r < A.n; ++r)
+    for (int k = A.rp[r]; k < A.rp[r + 1]; ++k) {
+      ci[(size_t)(k - A.rp[r]) * A.n + r] = A.ci[k];
+      v[(size_t)(k - A.rp[r]) * A.n + r] = A.v[k];
+    }
+}
 
 }  // namespace
 
@@ -110,6 +151,7 @@ struct hdgmg_ctx {
   std::vector<DevLevel> cr;
   std::vector<DevTransfer> tr;
   double* coarse_inv = nullptr;
+  float* coarse_inv32 = nullptr;
   int n0 = 0;
   // Krylov / Uzawa vectors
   double *x = nullptr, *r = nullptr, *r_old = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
@@ -289,6 +331,8 @@ hdgmg_status upload_level(hdgmg_ctx* ctx, const Level& L, int m, DevLevel& D) {
     TRY(dalloc(ctx, &D.Sp, (size_t)L.nc * fast_cell_words(nK)));
     TRY(dalloc(ctx, &D.yF, (size_t)L.nint * 2 * m2));
     D.bytes_cell = ((double)L.nc * fast_cell_words(nK) + 2.0 * ncd * m2) * 8.0 + L.nc * 12.0;
+    const double ws = ctx->opts.vcycle_precision == 1 ? 4.0 : 8.0;
+    D.bytes_cell_vc = (double)L.nc * fast_cell_words(nK) * ws + 2.0 * ncd * m2 * 8.0 + L.nc * 12.0;
     D.bytes_sum = 3.0 * L.nint * m2 * 8.0;
     const int NS = FAST_NF * m2;
     for (int cc = 0; cc < L.ncol; ++cc) {
@@ -308,6 +352,7 @@ hdgmg_status upload_level(hdgmg_ctx* ctx, const Level& L, int m, DevLevel& D) {
       D.pfc.push_back(dpf);
       D.Ppc.push_back(dPp);
       D.bytes_relax.push_back((double)np * NS * NS * 8.0 + np * FAST_NF * 4.0 + 5.0 * nfac * m2 * 8.0);
+      D.bytes_relax_vc.push_back((double)np * NS * NS * ws + np * FAST_NF * 4.0 + 5.0 * nfac * m2 * 8.0);
     }
   }
   TRY(dalloc(ctx, &D.u, (size_t)D.ndof));
@@ -349,6 +394,37 @@ hdgmg_status pack_fast(hdgmg_ctx* ctx, DevLevel& D) {
   return HDGMG_OK;
 }
 
+// FP32 copies of the operators a level's smoothing and residuals read.
+hdgmg_status make_f32(hdgmg_ctx* ctx, DevLevel& D) {
+  if (ctx->opts.vcycle_precision != 1) return HDGMG_OK;
+  D.f32 = true;
+  long nS = (long)D.nc * D.nK * D.nK;
+  TRY(dalloc(ctx, &D.S32, (size_t)nS));
+  launch_to_f32(ctx->st, nS, D.S, D.S32);
+  TRY(dalloc(ctx, &D.pinv32, (size_t)std::max(D.pinv_len, 1L)));
+  launch_to_f32(ctx->st, D.pinv_len, D.pinv, D.pinv32);
+  if (D.fast) {
+    long nSp = (long)D.nc * fast_cell_words(D.nK);
+    TRY(dalloc(ctx, &D.Sp32, (size_t)nSp));
+    launch_to_f32(ctx->st, nSp, D.Sp, D.Sp32);
+    const long NS = (long)FAST_NF * 2 * D.m;
+    D.Pp32.assign(D.Ppc.size(), nullptr);
+    for (size_t c = 0; c < D.Ppc.size(); ++c) {
+      long n = std::max(D.npc[c], 1) * NS * NS;
+      TRY(dalloc(ctx, &D.Pp32[c], (size_t)n));
+      launch_to_f32(ctx->st, n, D.Ppc[c], D.Pp32[c]);
+    }
+  }
+  HIPC(hipGetLastError());
+  return HDGMG_OK;
+}
+
+template <typename T>
+hdgmg_status upload_f32(hdgmg_ctx* ctx, float** p, const std::vector<T>& h) {
+  std::vector<float> f(h.begin(), h.end());
+  return upload(ctx, p, f);
+}
+
 // ------------------------------------------------------------ multigrid
 void sweep(hdgmg_ctx* ctx, DevLevel& D, double* x, const double* b, bool forward, int level) {
   const int nc = (int)D.colour_ptr.size() - 1;
@@ -357,38 +433,60 @@ void sweep(hdgmg_ctx* ctx, DevLevel& D, double* x, const double* b, bool forward
     if (D.fast) {
       // colour phase = cell apply (all cells) + patch relaxation (colour c)
       int t = kt_begin(ctx, level < 0 ? 1 : 2);
-      launch_cell_apply(ctx->st, 2 * D.m, D.nc, D.Sp, D.cdof, x, D.yF);
-      kt_end(ctx, level < 0 ? 1 : 2, t, D.bytes_cell);
+      if (D.f32)
+        launch_cell_apply<float>(ctx->st, 2 * D.m, D.nc, D.Sp32, D.cdof, x, D.yF);
+      else
+        launch_cell_apply<double>(ctx->st, 2 * D.m, D.nc, D.Sp, D.cdof, x, D.yF);
+      kt_end(ctx, level < 0 ? 1 : 2, t, D.bytes_cell_vc);
       t = kt_begin(ctx, level < 0 ? 0 : 2);
-      launch_patch_relax(ctx->st, 2 * D.m, D.npc[c], D.pfc[c], D.Ppc[c], b, D.yF, x);
-      kt_end(ctx, level < 0 ? 0 : 2, t, D.bytes_relax[c]);
+      if (D.f32)
+        launch_patch_relax<float>(ctx->st, 2 * D.m, D.npc[c], D.pfc[c], D.Pp32[c], b, D.yF, x);
+      else
+        launch_patch_relax<double>(ctx->st, 2 * D.m, D.npc[c], D.pfc[c], D.Ppc[c], b, D.yF, x);
+      kt_end(ctx, level < 0 ? 0 : 2, t, D.bytes_relax_vc[c]);
     } else {
       const int cls = level < 0 ? 0 : 2;
       int t = kt_begin(ctx, cls);
-      launch_gs(ctx->st, D.view(), D.colour_ptr[c], D.colour_ptr[c + 1], x, b);
-      kt_end(ctx, cls, t, level < 0 ? ctx->relax_bytes[c] : ctx->smooth_bytes[level][c]);
+      if (D.f32)
+        launch_gs<float>(ctx->st, D.view_t<float>(), D.colour_ptr[c], D.colour_ptr[c + 1], x, b);
+      else
+        launch_gs<double>(ctx->st, D.view_t<double>(), D.colour_ptr[c], D.colour_ptr[c + 1], x, b);
+      const double scale = D.f32 ? 0.5 : 1.0;  // operator words dominate the phase bytes
+      kt_end(ctx, cls, t, scale * (level < 0 ? ctx->relax_bytes[c] : ctx->smooth_bytes[level][c]));
     }
   }
 }
 
-// y = alpha A x + b on any level (streaming layout when available).
+// y = alpha A x + b on any level (streaming layout when available); vc:
+// read the preconditioner's storage (FP32 when so configured).
 void level_apply(hdgmg_ctx* ctx, DevLevel& D, const double* x, double* y, double alpha, const double* b,
-                 int cls) {
+                 int cls, bool vc) {
+  const bool f32 = vc && D.f32;
   if (D.fast) {
     int t = kt_begin(ctx, cls);
-    launch_cell_apply(ctx->st, 2 * D.m, D.nc, D.Sp, D.cdof, x, D.yF);
-    kt_end(ctx, cls, t, D.bytes_cell);
+    if (f32)
+      launch_cell_apply<float>(ctx->st, 2 * D.m, D.nc, D.Sp32, D.cdof, x, D.yF);
+    else
+      launch_cell_apply<double>(ctx->st, 2 * D.m, D.nc, D.Sp, D.cdof, x, D.yF);
+    kt_end(ctx, cls, t, f32 ? D.bytes_cell_vc : D.bytes_cell);
     launch_facet_sum(ctx->st, D.nint, 2 * D.m, D.yF, b, alpha, y);
   } else {
     int t = kt_begin(ctx, cls);
-    launch_apply(ctx->st, D.view(), x, y, alpha, b);
-    kt_end(ctx, cls, t, ctx->apply_bytes + (b ? D.ndof * 8.0 : 0.0));
+    if (f32) {
+      LevelViewT<float> v = D.view_t<float>();
+      launch_apply<float>(ctx->st, v, x, y, alpha, b);
+    } else {
+      LevelViewT<double> v = D.view_t<double>();
+      v.S = D.S;
+      launch_apply<double>(ctx->st, v, x, y, alpha, b);
+    }
+    kt_end(ctx, cls, t, (f32 ? 0.5 : 1.0) * ctx->apply_bytes + (b ? D.ndof * 8.0 : 0.0));
   }
 }
 
 // Skeleton apply on the order-k level, timed as class 1.
-void apply_k(hdgmg_ctx* ctx, const double* x, double* y, double alpha, const double* b) {
-  level_apply(ctx, ctx->K, x, y, alpha, b, 1);
+void apply_k(hdgmg_ctx* ctx, const double* x, double* y, double alpha, const double* b, bool vc = false) {
+  level_apply(ctx, ctx->K, x, y, alpha, b, 1, vc);
 }
 
 // Alg. 1 on lowest-order level l: u_l <- MG_h(l, g_l, u_l, m_l, q)
@@ -396,23 +494,34 @@ void mg_h(hdgmg_ctx* ctx, int l, int m_l) {
   DevLevel& D = ctx->cr[l];
   if (l <= ctx->Lc) {
     int t = kt_begin(ctx, 4);
+    const bool f32 = ctx->opts.vcycle_precision == 1;
     launch_coarse_cycle(ctx->st, ctx->coarse_desc, l, m_l, ctx->opts.vcycle_growth, ctx->opts.cycle,
-                        ctx->coarse_inv, ctx->n0, ctx->coarse_ns, ctx->coarse_lds);
+                        f32 ? (const void*)ctx->coarse_inv32 : (const void*)ctx->coarse_inv, ctx->n0,
+                        ctx->coarse_ns, ctx->coarse_lds, f32 ? 1 : 0);
     kt_end(ctx, 4, t, 0.0);
     return;
   }
   if (l == 0) {
-    launch_gemv_dense(ctx->st, ctx->n0, ctx->coarse_inv, D.g, D.u);
+    if (ctx->opts.vcycle_precision == 1)
+      launch_gemv_dense<float>(ctx->st, ctx->n0, ctx->coarse_inv32, D.g, D.u);
+    else
+      launch_gemv_dense<double>(ctx->st, ctx->n0, ctx->coarse_inv, D.g, D.u);
     return;
   }
   for (int s = 0; s < m_l; ++s) sweep(ctx, D, D.u, D.g, true, l);
-  level_apply(ctx, D, D.u, D.r, -1.0, D.g, 2);
+  level_apply(ctx, D, D.u, D.r, -1.0, D.g, 2, true);
   DevTransfer& T = ctx->tr[l];
   DevLevel& C = ctx->cr[l - 1];
-  launch_spmv(ctx->st, T.ncoarse, T.R_rp, T.R_ci, T.R_v, D.r, C.g, 0.0);
+  if (ctx->opts.vcycle_precision == 1)
+    launch_ell_spmv<float>(ctx->st, T.ncoarse, T.Rw, T.Re_ci, T.Re_v32, D.r, C.g, 0.0);
+  else
+    launch_ell_spmv<double>(ctx->st, T.ncoarse, T.Rw, T.Re_ci, T.Re_v, D.r, C.g, 0.0);
   launch_fill(ctx->st, C.ndof, 0.0, C.u);
   for (int n = 0; n < ctx->opts.cycle; ++n) mg_h(ctx, l - 1, ctx->opts.vcycle_growth * m_l);
-  launch_spmv(ctx->st, T.nfine, T.P_rp, T.P_ci, T.P_v, C.u, D.u, 1.0);
+  if (ctx->opts.vcycle_precision == 1)
+    launch_ell_spmv<float>(ctx->st, T.nfine, T.Pw, T.Pe_ci, T.Pe_v32, C.u, D.u, 1.0);
+  else
+    launch_ell_spmv<double>(ctx->st, T.nfine, T.Pw, T.Pe_ci, T.Pe_v, C.u, D.u, 1.0);
   for (int s = 0; s < m_l; ++s) sweep(ctx, D, D.u, D.g, false, l);
 }
 
@@ -477,7 +586,7 @@ void mg_hp_body(hdgmg_ctx* ctx, const double* r, double* z) {
   }
   launch_fill(ctx->st, KL.ndof, 0.0, z);
   for (int s = 0; s < ctx->opts.m_relax; ++s) sweep(ctx, KL, z, r, true, -1);
-  apply_k(ctx, z, KL.r, -1.0, r);
+  apply_k(ctx, z, KL.r, -1.0, r, true);
   launch_mode0_extract(ctx->st, KL.nint, KL.m, KL.r, DJ.g);
   launch_fill(ctx->st, DJ.ndof, 0.0, DJ.u);
   mg_h(ctx, ctx->J - 1, ctx->opts.m_smooth);
@@ -565,6 +674,20 @@ hdgmg_status build_transfers(hdgmg_ctx* ctx) {
     TRY(upload(ctx, &Tt.R_rp, R.rp));
     TRY(upload(ctx, &Tt.R_ci, R.ci));
     TRY(upload(ctx, &Tt.R_v, R.v));
+    std::vector<int> eci;
+    std::vector<double> ev;
+    to_ell(P, Tt.Pw, eci, ev);
+    TRY(upload(ctx, &Tt.Pe_ci, eci));
+    TRY(upload(ctx, &Tt.Pe_v, ev));
+    if (ctx->opts.vcycle_precision == 1) {
+      TRY(upload_f32(ctx, &Tt.Pe_v32, ev));
+      TRY(upload_f32(ctx, &Tt.P_v32, P.v));
+      TRY(upload_f32(ctx, &Tt.R_v32, R.v));
+    }
+    to_ell(R, Tt.Rw, eci, ev);
+    TRY(upload(ctx, &Tt.Re_ci, eci));
+    TRY(upload(ctx, &Tt.Re_v, ev));
+    if (ctx->opts.vcycle_precision == 1) TRY(upload_f32(ctx, &Tt.Re_v32, ev));
   }
   std::vector<double> inv;
   if (!coarse_inverse(ctx->lv[0], nu[0], ctx->beta, eps_inv, inv)) {
@@ -573,6 +696,7 @@ hdgmg_status build_transfers(hdgmg_ctx* ctx) {
   }
   ctx->n0 = 2 * ctx->lv[0].nint;
   TRY(upload(ctx, &ctx->coarse_inv, inv));
+  if (ctx->opts.vcycle_precision == 1) TRY(upload_f32(ctx, &ctx->coarse_inv32, inv));
   return HDGMG_OK;
 }
 
@@ -699,21 +823,32 @@ hdgmg_status build_coarse(hdgmg_ctx* ctx) {
     C.bitem = ti;
     TRY(upload(ctx, &tu, it_col));
     C.it_col = tu;
-    TRY(upload(ctx, &td, it_val));
-    C.it_val = td;
-    TRY(upload(ctx, &td, it_ainv));
-    C.it_ainv = td;
+    const bool f32 = ctx->opts.vcycle_precision == 1;
+    float* tf;
+    if (f32) {
+      TRY(upload_f32(ctx, &tf, it_val));
+      C.it_val = tf;
+      TRY(upload_f32(ctx, &tf, it_ainv));
+      C.it_ainv = tf;
+      TRY(upload_f32(ctx, &tf, rw_val));
+      C.rw_val = tf;
+    } else {
+      TRY(upload(ctx, &td, it_val));
+      C.it_val = td;
+      TRY(upload(ctx, &td, it_ainv));
+      C.it_ainv = td;
+      TRY(upload(ctx, &td, rw_val));
+      C.rw_val = td;
+    }
     TRY(upload(ctx, &ti, rw_col));
     C.rw_col = ti;
-    TRY(upload(ctx, &td, rw_val));
-    C.rw_val = td;
     const DevTransfer& T = ctx->tr[l];
     C.R_rp = T.R_rp;
     C.R_ci = T.R_ci;
-    C.R_v = T.R_v;
+    C.R_v = f32 ? (const void*)T.R_v32 : (const void*)T.R_v;
     C.P_rp = T.P_rp;
     C.P_ci = T.P_ci;
-    C.P_v = T.P_v;
+    C.P_v = f32 ? (const void*)T.P_v32 : (const void*)T.P_v;
   }
   std::vector<char> raw(sizeof(CoarseLevel) * desc.size());
   std::memcpy(raw.data(), desc.data(), raw.size());
@@ -765,6 +900,7 @@ void hdgmg_default_opts(hdgmg_opts* o) {
   o->uzawa_tol = 1e-10;
   o->coarse_dofs = 2048;
   o->stream_dofs = 200000;
+  o->vcycle_precision = 0;
 }
 
 const char* hdgmg_last_error(const hdgmg_ctx* ctx) {
@@ -816,7 +952,8 @@ hdgmg_status hdgmg_setup(const hdgmg_mesh* mesh, int k, double beta, const doubl
   if (opts) ctx->opts = *opts;
   if (ctx->opts.m_relax < 0 || ctx->opts.m_smooth < 1 || ctx->opts.cycle < 1 || ctx->opts.cycle > 2 ||
       ctx->opts.vcycle_growth < 1 || ctx->opts.max_it < 1 || ctx->opts.uzawa_max < 1 ||
-      ctx->opts.uzawa_max > HDGMG_MAX_UZAWA || !(ctx->opts.rtol >= 0) || !(ctx->opts.atol >= 0)) {
+      ctx->opts.uzawa_max > HDGMG_MAX_UZAWA || !(ctx->opts.rtol >= 0) || !(ctx->opts.atol >= 0) ||
+      ctx->opts.vcycle_precision < 0 || ctx->opts.vcycle_precision > 1) {
     g_setup_error = "invalid options";
     delete ctx;
     return HDGMG_EINVAL;
@@ -938,6 +1075,7 @@ hdgmg_status hdgmg_assemble(hdgmg_ctx* ctx) {
   TRY(batched(ctx, ctx->K.nc, ctx->k, EL_CONDENSE, nullptr, nullptr, nullptr, nullptr, nullptr));
   TRY(patch_inverses(ctx, ctx->K));
   TRY(pack_fast(ctx, ctx->K));
+  TRY(make_f32(ctx, ctx->K));
   TRY(build_transfers(ctx));
   for (int l = 0; l < ctx->J; ++l) {
     DevLevel& D = ctx->cr[l];
@@ -945,6 +1083,7 @@ hdgmg_status hdgmg_assemble(hdgmg_ctx* ctx) {
     HIPC(hipGetLastError());
     if (l > 0) TRY(patch_inverses(ctx, D));
     if (l > 0) TRY(pack_fast(ctx, D));
+    if (l > 0) TRY(make_f32(ctx, D));
   }
   TRY(build_coarse(ctx));
   HIPC(hipStreamSynchronize(ctx->st));

@@ -233,3 +233,44 @@ def test_preconditioner_graph_replays():
         G.apply(r_dev)                      # eager work between replays
         G.precondition(r_dev, out=z_dev)
         assert rel(host(z_dev), O.prec(r)) < 1e-10, rep
+
+
+MIXED = {
+    # name: (base case, extra options)
+    "k2_mixed_stream": ("k2", dict(vcycle_precision=1, stream_dofs=0, coarse_dofs=400)),
+    "k1_mixed_per_level": ("k1", dict(vcycle_precision=1, coarse_dofs=0)),
+    "k3_mixed_gs": ("k3", dict(vcycle_precision=1)),
+    "gamma1e4_mixed": ("beta0_gamma1e4", dict(vcycle_precision=1, stream_dofs=0)),
+}
+
+
+@pytest.mark.parametrize("name", list(MIXED))
+def test_mixed_precision_preconditioner_and_solve(name):
+    """FP32 storage of every preconditioner operator (vectors and the outer
+    flexible CG in FP64): z = MG_hp(r) agrees with the FP64 oracle to FP32
+    storage rounding amplified by the AL weight (1e-4 relative bound), and the
+    inner solve still reaches relative residual 1e-8 on the FP64 operator
+    (checked with the oracle's assembled A^eps), in at most 2 more iterations
+    than the FP64 oracle."""
+    base, extra = MIXED[name]
+    c, t, nref, k, nu, beta, gamma, kw = case(base)
+    _note(f"[mixed] {name}")
+    O = oracle_setup(base, c, t, nref, k, nu, beta, gamma, **kw)
+    G = gpu_solver(c, t, nref, k, nu, beta, gamma, **{**kw, **extra})
+    r = synth.uniform_pm1(22, 0, (G.n_skel,))
+    z = host(G.precondition(dev(r)))
+    err = rel(z, O.prec(r))
+    _note(f"  preconditioner rel. difference to FP64 oracle: {err:.2e}")
+    assert err < 1e-4
+    f = synth.source_uniform(0, 1, G.n_cells, G.n_q)[0]
+    g = O.prob.rhs(f)
+    x_o, its_o, _ = O.inner(g, atol=0.0)
+    import paper_2303_06762_amd as hd
+    x, its, relres, st = G.inner_solve(dev(g))
+    x = host(x)
+    true_res = np.linalg.norm(g - O.Aeps @ x) / np.linalg.norm(g)
+    _note(f"  its {its} (FP64 oracle {its_o}), true rel. residual {true_res:.2e}, "
+          f"solution rel. difference {np.linalg.norm(x - x_o) / np.linalg.norm(x_o):.2e}")
+    assert st == 0
+    assert true_res <= 1.5e-8
+    assert its <= its_o + 2

@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts_match_header():
     # hdgmg_mesh: int, int, ptr, int, ptr, int; hdgmg_opts; hdgmg_info
     assert ctypes.sizeof(hd.Mesh) == 40
-    assert ctypes.sizeof(hd.Opts) == 4 * 4 + 8 * 2 + 4 * 2 + 8 + 8
+    assert ctypes.sizeof(hd.Opts) == 4 * 4 + 8 * 2 + 4 * 2 + 8 + 4 * 3 + 4
     assert ctypes.sizeof(hd.Info) == 4 + 64 * 4 + 4 + 64 * 8 * 2
 
 
