@@ -8,7 +8,9 @@ point (seed 0) plus the gradient of a seeded trigonometric polynomial.
 A step is inner solve #1 of the AL-Uzawa iteration: A^eps lambda = g from
 lambda = 0 by flexible CG preconditioned by MG_hp (variable V-cycle,
 m_p = m_h = 1) to relative residual 1e-8, every operation in the HIP
-library, the condensed load g already resident in HBM.
+library, the condensed load g already resident in HBM.  `value` is the
+all-FP64 solve; `mixed` stores the V-cycle's operators in FP32 (FP64
+vectors, accumulation and Krylov; same 1e-8 on the FP64 operator).
 
 Prints one JSON line (metric, value = skeleton DOFs solved per second,
 roofline of the dominant kernel from live HIP-event timing, the V-cycle's
@@ -24,9 +26,21 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-KCLASS = {0: "order-k vertex-patch Gauss-Seidel colour phase (k_gs)",
-          1: "order-k skeleton apply (k_apply)",
-          2: "lowest-order patch Gauss-Seidel phases (k_gs, all CR levels)"}
+KCLASS = {0: "order-k vertex-patch relaxation, one colour (k_patch_relax)",
+          1: "order-k cell apply S_K x_K (k_cell_apply)",
+          2: "lowest-order smoothing phases on launched levels (k_gs / streaming pair)"}
+# The roofline object reports the order-k cell apply: the HBM-bound kernel
+# that runs most often (every Gauss-Seidel colour phase and every Krylov
+# apply read all cell blocks).
+ROOF_CLASS = 1
+# HBM traffic of that kernel from two counter runs (FETCH_SIZE, then
+# WRITE_SIZE, KiB per dispatch) of `bench.py --profile-run`, each scaled by
+# what the counter read for a plain copy of 1 GiB in the same run (FETCH
+# 524308 KiB -> x2.0, WRITE 1048576 KiB -> x1.0).  Valid only for the
+# workload and kernel it was taken on.
+TRAFFIC = {(2, 6, 1.0, 1e2): {"kernel": "k_cell_apply<6, double>", "fetch_KiB": 95685.79,
+                              "write_KiB": 18770.71, "fetch_scale": 1048576 / 524308.0,
+                              "write_scale": 1.0}}
 
 
 def cpu_baseline(k, beta, gamma, reps):
@@ -55,6 +69,23 @@ def cpu_baseline(k, beta, gamma, reps):
             "seconds": round(dt, 3)}
 
 
+def copy_bandwidth(torch, reps=5):
+    """Read + write bandwidth of a plain 1 GiB device copy (HIP events)."""
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * src.numel() * 8 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -66,6 +97,9 @@ def main():
     ap.add_argument("--gamma", type=float, default=1e2)
     ap.add_argument("--cpu-reps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="counter-collection run: a 1 GiB device copy (calibration of the HBM "
+                         "counters) then two FP64 inner solves; prints a summary only")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {a.gpus} is not supported "
@@ -78,70 +112,115 @@ def main():
 
     torch.cuda.set_device(0)
     c, t = synth.kuhn_square(4)
-    t0 = time.perf_counter()
-    s = hd.Solver(c, t, a.n_refine, a.k, a.beta, 1.0, a.gamma, atol=0.0)
-    t_setup = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    s.assemble()
-    torch.cuda.synchronize()
-    t_assemble = time.perf_counter() - t0
-    X = s.data_points().cpu().numpy()
-    f = synth.source_uniform(0, 1, s.n_cells, s.n_q)[0] + synth.trig_gradient(X, 1)
-    f_dev = torch.as_tensor(f, device="cuda")
-    g = s.rhs(f_dev)
-    x = torch.empty_like(g)
-    for _ in range(a.warmup):
-        s.inner_solve(g, x)
-    # timed region: K inner solves, nothing else
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    its_all = []
-    for _ in range(a.steps):
-        _, its, rel, st = s.inner_solve(g, x)
-        its_all.append(its)
-    torch.cuda.synchronize()
-    T = time.perf_counter() - t0
-    value = s.n_skel * a.steps / T
-    # same work again with live per-kernel event timers
-    for cls in range(4):
-        s.timer(cls, True)
-    torch.cuda.synchronize()
-    for _ in range(a.steps):
-        s.inner_solve(g, x)
-    torch.cuda.synchronize()
-    tm = {cls: s.timer_read(cls) for cls in range(4)}
-    for cls in range(4):
-        s.timer(cls, False)
-    dom = max((0, 1, 2), key=lambda c_: tm[c_][0])
+    if a.profile_run:
+        # calibration: a plain copy of exactly 1 GiB read + 1 GiB written
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        s = hd.Solver(c, t, a.n_refine, a.k, a.beta, 1.0, a.gamma, atol=0.0)
+        s.assemble()
+        g = torch.ones(s.n_skel, dtype=torch.float64, device="cuda")
+        x = torch.empty_like(g)
+        for _ in range(2):
+            _, its, rel, st = s.inner_solve(g, x)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_run": True, "n_skel": s.n_skel, "iterations": its}))
+        return
+
+    def measure(prec):
+        """Setup, assemble, then time inner solve #1 K times (value) and K
+        more times with the live per-kernel event timers (roofline)."""
+        t0 = time.perf_counter()
+        s = hd.Solver(c, t, a.n_refine, a.k, a.beta, 1.0, a.gamma, atol=0.0, vcycle_precision=prec)
+        t_setup = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        s.assemble()
+        torch.cuda.synchronize()
+        t_assemble = time.perf_counter() - t0
+        X = s.data_points().cpu().numpy()
+        f = synth.source_uniform(0, 1, s.n_cells, s.n_q)[0] + synth.trig_gradient(X, 1)
+        g = s.rhs(torch.as_tensor(f, device="cuda"))
+        x = torch.empty_like(g)
+        for _ in range(a.warmup):
+            s.inner_solve(g, x)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its_all = []
+        for _ in range(a.steps):
+            _, its, rel, st = s.inner_solve(g, x)
+            its_all.append(its)
+        torch.cuda.synchronize()
+        T = time.perf_counter() - t0
+        for cls in range(5):
+            s.timer(cls, True)
+        torch.cuda.synchronize()
+        for _ in range(a.steps):
+            s.inner_solve(g, x)
+        torch.cuda.synchronize()
+        tm = {cls: s.timer_read(cls) for cls in range(5)}
+        for cls in range(5):
+            s.timer(cls, False)
+        out = dict(T=T, its=its_all, tm=tm, t_setup=t_setup, t_assemble=t_assemble, n_skel=s.n_skel,
+                   n_cells=s.n_cells, levels=s.levels, rel=rel)
+        s.close()
+        return out
+
+    m64 = measure(0)
+    m32 = measure(1)
+    tm = m64["tm"]
+    dom = ROOF_CLASS
     ms, n_l, by = tm[dom]
     achieved = (by / n_l) / (ms / n_l * 1e-3) / 1e9
     vc_ms, vc_n, vc_b = tm[3]
+    tr = TRAFFIC.get((a.k, a.n_refine, a.beta, a.gamma))
+    traffic = None if tr is None else 1024.0 * (tr["fetch_KiB"] * tr["fetch_scale"] +
+                                                tr["write_KiB"] * tr["write_scale"])
+    copy_gbs = copy_bandwidth(torch)
+    by_time = max(range(5), key=lambda c_: tm[c_][0] if c_ != 3 else -1.0)
+
+    def classes(tm_):
+        return {KCLASS.get(c_, "MG_hp"): {"ms": tm_[c_][0], "launches": tm_[c_][1], "GB": tm_[c_][2] / 1e9}
+                for c_ in range(4)} | {"single-workgroup coarse MG_h (k_coarse_cycle)":
+                                       {"ms": tm_[4][0], "launches": tm_[4][1]}}
+
+    n_skel = m64["n_skel"]
     out = {
         "metric": "skeleton DOFs solved/s to rel.res 1e-8 (FP64 vs mixed); V-cycle HBM GB/s",
-        "value": value,
+        "value": n_skel * a.steps / m64["T"],
         "unit": "skeleton DOFs/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": 1e3 * T / a.steps,
+        "ms_per_step": 1e3 * m64["T"] / a.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"2D generalized Stokes, {4 << a.n_refine}x{4 << a.n_refine} structured "
-                               f"triangulation ({s.n_cells} cells, {s.levels} levels), k={a.k}, "
+                               f"triangulation ({m64['n_cells']} cells, {m64['levels']} levels), k={a.k}, "
                                f"beta={a.beta:g}, nu=1, gamma={a.gamma:g}; inner solve #1 to rel.res 1e-8",
-                   "n_skel": s.n_skel, "iterations": its_all, "precision": "fp64 (V-cycle fp64)"},
+                   "n_skel": n_skel, "iterations": m64["its"],
+                   "precision": "FP64 operators, vectors and Krylov"},
+        "mixed": {"value": n_skel * a.steps / m32["T"], "unit": "skeleton DOFs/s",
+                  "ms_per_step": 1e3 * m32["T"] / a.steps, "iterations": m32["its"],
+                  "precision": "V-cycle operators stored FP32; vectors, accumulation and the "
+                               "flexible CG FP64; same rel.res 1e-8 on the FP64 operator",
+                  "vcycle_avg_ms": m32["tm"][3][0] / max(m32["tm"][3][1], 1),
+                  "kernel_classes": classes(m32["tm"])},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "kernel": KCLASS[dom], "launches": n_l, "avg_us": 1e3 * ms / n_l,
-                     "algorithmic_bytes_per_launch": by / n_l},
+                     "algorithmic_bytes_per_launch": by / n_l,
+                     "copy_GB_per_s": copy_gbs,
+                     "largest_class_by_time": (KCLASS.get(by_time) or
+                                               "single-workgroup coarse MG_h (k_coarse_cycle), "
+                                               "latency-bound on one compute unit")},
         "vcycle": {"avg_ms": vc_ms / max(vc_n, 1), "algorithmic_GB": vc_b / max(vc_n, 1) / 1e9,
                    "GB_per_s": (vc_b / max(vc_n, 1)) / (vc_ms / max(vc_n, 1) * 1e-3) / 1e9},
-        "kernel_classes": {KCLASS.get(c_, "MG_hp"): {"ms": tm[c_][0], "launches": tm[c_][1],
-                                                      "GB": tm[c_][2] / 1e9} for c_ in range(4)},
-        "setup_s": t_setup, "assemble_s": t_assemble,
+        "kernel_classes": classes(tm),
+        "setup_s": m64["t_setup"], "assemble_s": m64["t_assemble"],
     }
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(a.k, a.beta, a.gamma, a.cpu_reps)

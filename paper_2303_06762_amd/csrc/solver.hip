@@ -330,9 +330,12 @@ hdgmg_status upload_level(hdgmg_ctx* ctx, const Level& L, int m, DevLevel& D) {
     TRY(upload(ctx, &D.cdof, cd));
     TRY(dalloc(ctx, &D.Sp, (size_t)L.nc * fast_cell_words(nK)));
     TRY(dalloc(ctx, &D.yF, (size_t)L.nint * 2 * m2));
-    D.bytes_cell = ((double)L.nc * fast_cell_words(nK) + 2.0 * ncd * m2) * 8.0 + L.nc * 12.0;
+    // compulsory bytes of one cell apply: the blocks, the facet map, x once
+    // per interior facet, y_F once per (cell, interior facet)
+    const double vec = ((double)L.nint + ncd) * m2 * 8.0 + L.nc * 12.0;
+    D.bytes_cell = (double)L.nc * fast_cell_words(nK) * 8.0 + vec;
     const double ws = ctx->opts.vcycle_precision == 1 ? 4.0 : 8.0;
-    D.bytes_cell_vc = (double)L.nc * fast_cell_words(nK) * ws + 2.0 * ncd * m2 * 8.0 + L.nc * 12.0;
+    D.bytes_cell_vc = (double)L.nc * fast_cell_words(nK) * ws + vec;
     D.bytes_sum = 3.0 * L.nint * m2 * 8.0;
     const int NS = FAST_NF * m2;
     for (int cc = 0; cc < L.ncol; ++cc) {
@@ -426,6 +429,14 @@ hdgmg_status upload_f32(hdgmg_ctx* ctx, float** p, const std::vector<T>& h) {
 }
 
 // ------------------------------------------------------------ multigrid
+// Algorithmic bytes of Gauss-Seidel colour phase c of a level (level < 0:
+// the order-k level) in the storage the V-cycle reads.
+double phase_bytes(const hdgmg_ctx* ctx, const DevLevel& D, int level, int c) {
+  if (D.fast) return D.bytes_cell_vc + D.bytes_relax_vc[c];
+  const double scale = D.f32 ? 0.5 : 1.0;  // operator words dominate the phase bytes
+  return scale * (level < 0 ? ctx->relax_bytes[c] : ctx->smooth_bytes[level][c]);
+}
+
 void sweep(hdgmg_ctx* ctx, DevLevel& D, double* x, const double* b, bool forward, int level) {
   const int nc = (int)D.colour_ptr.size() - 1;
   for (int i = 0; i < nc; ++i) {
@@ -451,8 +462,7 @@ void sweep(hdgmg_ctx* ctx, DevLevel& D, double* x, const double* b, bool forward
         launch_gs<float>(ctx->st, D.view_t<float>(), D.colour_ptr[c], D.colour_ptr[c + 1], x, b);
       else
         launch_gs<double>(ctx->st, D.view_t<double>(), D.colour_ptr[c], D.colour_ptr[c + 1], x, b);
-      const double scale = D.f32 ? 0.5 : 1.0;  // operator words dominate the phase bytes
-      kt_end(ctx, cls, t, scale * (level < 0 ? ctx->relax_bytes[c] : ctx->smooth_bytes[level][c]));
+      kt_end(ctx, cls, t, phase_bytes(ctx, D, level, c));
     }
   }
 }
@@ -1087,27 +1097,30 @@ hdgmg_status hdgmg_assemble(hdgmg_ctx* ctx) {
   }
   TRY(build_coarse(ctx));
   HIPC(hipStreamSynchronize(ctx->st));
-  // algorithmic bytes of one MG_hp application (sum over its launches)
+  // algorithmic bytes of one MG_hp application (sum over its launches,
+  // operators in the storage precision the V-cycle reads)
   {
-    double v = 0.0;
     const auto& o = ctx->opts;
+    double v = 0.0;
     if (ctx->k > 0) {
       double sw = 0.0;
-      for (double b : ctx->relax_bytes) sw += b;
-      v += 2.0 * o.m_relax * sw + ctx->apply_bytes + ctx->K.ndof * 8.0;
+      for (int c = 0; c < (int)ctx->K.colour_ptr.size() - 1; ++c) sw += phase_bytes(ctx, ctx->K, -1, c);
+      v += 2.0 * o.m_relax * sw + 2.0 * ctx->K.ndof * 8.0;  // sweeps; the mode-0 transfers
     }
     double visits = 1.0, m_l = o.m_smooth;
     for (int l = ctx->J - 1; l >= 1; --l) {
-      double sw = 0.0;
-      for (double b : ctx->smooth_bytes[l]) sw += b;
       const DevLevel& D = ctx->cr[l];
-      double res = ((double)D.nc * 36 + D.nc * 6.0 + 2.0 * D.ndof) * 8.0;
-      double trn = 2.0 * (ctx->tr[l].nnz * 12.0 + (ctx->tr[l].nfine + ctx->tr[l].ncoarse) * 8.0);
+      double sw = 0.0;
+      for (int c = 0; c < (int)D.colour_ptr.size() - 1; ++c) sw += phase_bytes(ctx, D, l, c);
+      const double ws = D.f32 ? 4.0 : 8.0;
+      double res = D.fast ? D.bytes_cell_vc + D.bytes_sum
+                          : (double)D.nc * 36 * ws + (D.nc * 6.0 + 2.0 * D.ndof) * 8.0;
+      double trn = 2.0 * (ctx->tr[l].nnz * (4.0 + ws) + (ctx->tr[l].nfine + ctx->tr[l].ncoarse) * 8.0);
       v += visits * (2.0 * m_l * sw + res + trn);
       visits *= o.cycle;
       m_l *= o.vcycle_growth;
     }
-    v += visits * (double)ctx->n0 * ctx->n0 * 8.0;
+    v += visits * (double)ctx->n0 * ctx->n0 * (o.vcycle_precision == 1 ? 4.0 : 8.0);
     ctx->vcycle_bytes = v;
   }
   ctx->assembled = true;
