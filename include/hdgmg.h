@@ -151,6 +151,29 @@ hdgmg_status hdgmg_assemble(hdgmg_ctx* ctx);
 hdgmg_status hdgmg_solve(hdgmg_ctx* ctx, const double* f_qp, double* u_qp,
                          double* p_qp, double* state, hdgmg_info* info);
 
+/* Adjoint solve for a functional J(u_qp) of the velocity at the data points
+ * (not in the paper; derived from the scheme of Sec. 3.2, whose system is a
+ * symmetric saddle point in which the viscosity enters only through the
+ * nu-weighted lifting energy of each cell).
+ *   f_qp   device [n_cells][n_q][2], input: the forward source
+ *   state  device [N_skel + n_cells], input: the forward state written by
+ *          hdgmg_solve for f_qp (the forward solution is checkpointed as
+ *          this state; no Krylov data is kept)
+ *   gu_qp  device [n_cells][n_q][2], input: dJ/du_qp
+ *   gf_qp  device [n_cells][n_q][2], output: dJ/df_qp = w_q |K| u_adj(x_q),
+ *          w_q the data-rule weights (sum 1) and |K| the cell area
+ *   gnu    device [n_cells] (finest cells), ACCUMULATED, may be NULL:
+ *          gnu[K] += dJ/dnu_K = -(Lift(u, uhat), Lift(u_adj, uhat_adj))_K
+ *   adj_state device [N_skel + n_cells], output, may be NULL: the adjoint state
+ *   info   host, may be NULL: the adjoint solve's Uzawa / inner iterations
+ * The adjoint state solves the forward system (same AL-Uzawa, flexible CG
+ * and MG_hp) with the load v -> sum_{K,q} gu_qp . v(x_q).  gf_qp must not
+ * alias the inputs.  Returns as hdgmg_solve; outputs are undefined on a
+ * negative status. */
+hdgmg_status hdgmg_solve_adjoint(hdgmg_ctx* ctx, const double* f_qp, const double* state,
+                                 const double* gu_qp, double* gf_qp, double* gnu,
+                                 double* adj_state, hdgmg_info* info);
+
 /* Condensed load g (length N_skel, device, output) of f_qp (device), the
  * right-hand side F_{k,h} of stOptForm. */
 hdgmg_status hdgmg_rhs(hdgmg_ctx* ctx, const double* f_qp, double* g);

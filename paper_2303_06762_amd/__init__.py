@@ -44,7 +44,8 @@ class HdgmgError(RuntimeError):
         self.status = status
 
 
-SYMBOLS = ["hdgmg_default_opts", "hdgmg_setup", "hdgmg_assemble", "hdgmg_solve", "hdgmg_rhs",
+SYMBOLS = ["hdgmg_default_opts", "hdgmg_setup", "hdgmg_assemble", "hdgmg_solve",
+           "hdgmg_solve_adjoint", "hdgmg_rhs",
            "hdgmg_apply", "hdgmg_precondition", "hdgmg_inner_solve", "hdgmg_recover",
            "hdgmg_query", "hdgmg_export", "hdgmg_kernel_timer", "hdgmg_kernel_timer_read",
            "hdgmg_last_error", "hdgmg_destroy"]
@@ -68,6 +69,8 @@ def lib():
     L.hdgmg_assemble.restype = i32
     L.hdgmg_solve.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(Info)]
     L.hdgmg_solve.restype = i32
+    L.hdgmg_solve_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(Info)]
+    L.hdgmg_solve_adjoint.restype = i32
     for name in ("hdgmg_rhs", "hdgmg_apply", "hdgmg_precondition"):
         getattr(L, name).argtypes = [vp, vp, vp]
         getattr(L, name).restype = i32
@@ -208,6 +211,25 @@ class Solver:
                  dp_l2=list(info.dp_l2[:n]))
         return u, p, state, d, st
 
+    def solve_adjoint(self, f_qp, state, gu_qp, gnu=None, adj_state=None):
+        """Adjoint of solve() for dJ/du_qp = gu_qp: returns (gf_qp, gnu,
+        adj_state, info dict, status); gnu (n_cells) is accumulated into
+        when given, else a new zeroed tensor."""
+        t = self.torch
+        gf = t.empty((self.n_cells, self.n_q, 2), dtype=t.float64, device="cuda")
+        if gnu is None:
+            gnu = t.zeros(self.n_cells, dtype=t.float64, device="cuda")
+        if adj_state is None:
+            adj_state = self._vec(self.n_skel + self.n_cells)
+        info = Info()
+        st = self._check(lib().hdgmg_solve_adjoint(self._h, _ptr(f_qp), _ptr(state), _ptr(gu_qp), _ptr(gf),
+                                                   _ptr(gnu), _ptr(adj_state), ctypes.byref(info)),
+                         allow=(0, 1))
+        n = info.uzawa_steps
+        d = dict(uzawa_steps=n, its=list(info.its[:n]), rel_res=list(info.rel_res[:n]),
+                 dp_l2=list(info.dp_l2[:n]))
+        return gf, gnu, adj_state, d, st
+
     def timer(self, kernel_class, enable=True):
         """Enable/disable the live event timer of a kernel class (see hdgmg.h)."""
         self._check(lib().hdgmg_kernel_timer(self._h, kernel_class, int(enable)))
@@ -232,3 +254,51 @@ class Solver:
             out = self.torch.empty((self.query(8, level), 6, 6), dtype=self.torch.float64, device="cuda")
         self._check(lib().hdgmg_export(self._h, what, level, _ptr(out), out.numel() * 8))
         return out
+
+
+def _make_function():
+    import torch
+
+    class StokesSolve(torch.autograd.Function):
+        """u_qp = solve(f_qp; nu) for a batch of sources [nrhs][n_cells][n_q][2]
+        on an assembled Solver.  `nu` [n_cells] must hold the per-cell
+        viscosities the Solver was set up with; it is an input only so that
+        autograd can return dJ/dnu (summed over the batch).  The forward
+        states are kept for the adjoint (no Krylov data)."""
+
+        @staticmethod
+        def forward(ctx, solver, f_qp, nu):
+            us, states = [], []
+            for f in f_qp:
+                f = f.contiguous()
+                u, _, state, _, _ = solver.solve(f)
+                us.append(u)
+                states.append(state)
+            ctx.solver = solver
+            ctx.save_for_backward(f_qp, torch.stack(states))
+            return torch.stack(us)
+
+        @staticmethod
+        def backward(ctx, gu):
+            f_qp, states = ctx.saved_tensors
+            solver = ctx.solver
+            gnu = torch.zeros(solver.n_cells, dtype=torch.float64, device=f_qp.device)
+            gfs = []
+            for i in range(f_qp.shape[0]):
+                gf, _, _, _, _ = solver.solve_adjoint(f_qp[i].contiguous(), states[i], gu[i].contiguous(),
+                                                      gnu=gnu)
+                gfs.append(gf)
+            return None, torch.stack(gfs), gnu
+
+    return StokesSolve
+
+
+_STOKES_SOLVE = None
+
+
+def stokes_solve(solver, f_qp, nu):
+    """Differentiable batched solve: u_qp = stokes_solve(solver, f_qp, nu)."""
+    global _STOKES_SOLVE
+    if _STOKES_SOLVE is None:
+        _STOKES_SOLVE = _make_function()
+    return _STOKES_SOLVE.apply(solver, f_qp, nu)

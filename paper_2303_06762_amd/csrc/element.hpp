@@ -217,7 +217,7 @@ HDI long element_ws_size(int k) {
   n += (long)D.nz * D.nz;       // H
   n += (long)D.nN * D.na;       // N
   n += (long)D.nP * D.na;       // Dr
-  n += D.na;                    // F
+  n += 2L * D.na;               // F (two loads for EL_GRADNU)
   n += (long)D.nkkt * D.nkkt;   // KKT
   n += D.nkkt;                  // pivots
   n += (long)D.nkkt * D.nK;     // right-hand sides / solutions
@@ -225,16 +225,21 @@ HDI long element_ws_size(int k) {
   return n;
 }
 
-enum { EL_CONDENSE = 0, EL_LOAD = 1, EL_RECOVER = 2 };
+enum { EL_CONDENSE = 0, EL_LOAD = 1, EL_RECOVER = 2, EL_GRADNU = 3 };
 
 // The local solve of one cell.  Returns 0 on success, 1 if the KKT matrix
 // is singular.  Inputs/outputs by mode:
 //   EL_CONDENSE: out = S^eps [nK][nK] (row-major)
 //   EL_LOAD:     f [nq][2] at the data points; out = g [nK]
 //   EL_RECOVER:  f, lam [nK], p0; out = u [nq][2] then p [nq]
+//   EL_GRADNU:   two local states, (f, lam) and (f2, lam2); out[0] =
+//                -(Lift(z), Lift(z2))_K, the derivative with respect to this
+//                cell's viscosity of the adjoint-weighted residual (the only
+//                nu-dependent term of the element energy is nu ||Lift||^2)
 HDI int element_local(const QuadTables& Q, const CellGeom& g, double nu, double beta,
                       double eps_inv, int mode, const double* f, const double* lam,
-                      double p0, WS w, double* out) {
+                      double p0, WS w, double* out, const double* f2 = nullptr,
+                      const double* lam2 = nullptr) {
   const Dims D = dims_of(Q.k);
   const int nP = D.nP, na = D.na, nz = D.nz, m = D.m, nK = D.nK, nN = D.nN, nkkt = D.nkkt;
   long o = 0;
@@ -251,7 +256,7 @@ HDI int element_local(const QuadTables& Q, const CellGeom& g, double nu, double 
   WS Dr{w.p + o * w.s, w.s};
   o += (long)nP * na;
   WS F{w.p + o * w.s, w.s};
-  o += na;
+  o += 2L * na;
   WS Kk{w.p + o * w.s, w.s};
   o += (long)nkkt * nkkt;
   WS piv{w.p + o * w.s, w.s};
@@ -265,7 +270,7 @@ HDI int element_local(const QuadTables& Q, const CellGeom& g, double nu, double 
   for (long i = 0; i < (long)nz * nz; ++i) H[i] = 0.0;
   for (long i = 0; i < (long)nN * na; ++i) Nm[i] = 0.0;
   for (long i = 0; i < (long)nP * na; ++i) Dr[i] = 0.0;
-  for (int i = 0; i < na; ++i) F[i] = 0.0;
+  for (int i = 0; i < 2 * na; ++i) F[i] = 0.0;
   for (int i = 0; i < nP; ++i) mean[i] = 0.0;
 
   double u[2 * 40], gr[4 * 40], mono[16];
@@ -290,6 +295,7 @@ HDI int element_local(const QuadTables& Q, const CellGeom& g, double nu, double 
       for (int b = 0; b <= a; ++b)
         H[(long)a * nz + b] += beta * wt * (u[2 * a] * u[2 * b] + u[2 * a + 1] * u[2 * b + 1]);
       if (mode != EL_CONDENSE) F[a] += wt * (f[2 * q] * u[2 * a] + f[2 * q + 1] * u[2 * a + 1]);
+      if (mode == EL_GRADNU) F[na + a] += wt * (f2[2 * q] * u[2 * a] + f2[2 * q + 1] * u[2 * a + 1]);
     }
   }
   for (int a = 0; a < na; ++a)
@@ -397,7 +403,7 @@ HDI int element_local(const QuadTables& Q, const CellGeom& g, double nu, double 
     }
   }
   // ---- right-hand sides
-  int ncol = mode == EL_CONDENSE ? nK : 1;
+  int ncol = mode == EL_CONDENSE ? nK : mode == EL_GRADNU ? 2 : 1;
   for (long i = 0; i < (long)nkkt * ncol; ++i) Bx[i] = 0.0;
   if (mode == EL_CONDENSE) {
     for (int i = 0; i < 3; ++i)
@@ -407,14 +413,18 @@ HDI int element_local(const QuadTables& Q, const CellGeom& g, double nu, double 
         for (int a = 0; a < na; ++a) Bx[(long)a * ncol + lt] = -H[(long)a * nz + na + i * m + j];
       }
   } else {
-    for (int a = 0; a < na; ++a) Bx[(long)a * ncol] = F[a];
-    if (mode == EL_RECOVER) {
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < m; ++j) {
-          double cn = lam[(i * 2 + 0) * m + j], ct = lam[(i * 2 + 1) * m + j];
-          Bx[(long)(na + i * m + j) * ncol] += cn;
-          for (int a = 0; a < na; ++a) Bx[(long)a * ncol] -= H[(long)a * nz + na + i * m + j] * ct;
-        }
+    for (int cc = 0; cc < ncol; ++cc)
+      for (int a = 0; a < na; ++a) Bx[(long)a * ncol + cc] = F[cc * na + a];
+    if (mode == EL_RECOVER || mode == EL_GRADNU) {
+      for (int cc = 0; cc < ncol; ++cc) {
+        const double* lm = cc == 0 ? lam : lam2;
+        for (int i = 0; i < 3; ++i)
+          for (int j = 0; j < m; ++j) {
+            double cn = lm[(i * 2 + 0) * m + j], ct = lm[(i * 2 + 1) * m + j];
+            Bx[(long)(na + i * m + j) * ncol + cc] += cn;
+            for (int a = 0; a < na; ++a) Bx[(long)a * ncol + cc] -= H[(long)a * nz + na + i * m + j] * ct;
+          }
+      }
     }
   }
   // apply the row permutation, then forward / backward substitution
@@ -475,6 +485,27 @@ HDI int element_local(const QuadTables& Q, const CellGeom& g, double nu, double 
           out[(i1 * 2 * m) * nK + i2 * 2 * m] +=
               eps_inv / g.area * (g.sigma[i1] * g.len[i1]) * (g.sigma[i2] * g.len[i2]);
     }
+  } else if (mode == EL_GRADNU) {
+    // -(Lift z, Lift z2)_K = -sum_ij (L_M^-1 R_ij z) . (L_M^-1 R_ij z2), with
+    // z = (interior RT coefficients, tangential facet traces) and L_M the
+    // Cholesky factor of the P^k mass matrix (held in M)
+    double s = 0.0;
+    for (int ij = 0; ij < 4; ++ij) {
+      for (int cc = 0; cc < 2; ++cc) {
+        const double* lm = cc == 0 ? lam : lam2;
+        for (int r = 0; r < nP; ++r) {
+          const long row = ((long)ij * nP + r) * nz;
+          double v = 0.0;
+          for (int a = 0; a < na; ++a) v += R[row + a] * Bx[(long)a * ncol + cc];
+          for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < m; ++j) v += R[row + na + i * m + j] * lm[(i * 2 + 1) * m + j];
+          for (int p = 0; p < r; ++p) v -= M[r * nP + p] * Y[(long)cc * nP + p];
+          Y[(long)cc * nP + r] = v / M[r * nP + r];
+        }
+      }
+      for (int r = 0; r < nP; ++r) s += Y[r] * Y[(long)nP + r];
+    }
+    out[0] = -s;
   } else {
     // recovery at the data points
     for (int q = 0; q < Q.nq; ++q) {

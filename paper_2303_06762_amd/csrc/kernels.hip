@@ -70,6 +70,54 @@ __global__ void k_recover(QuadTables Q, const double* __restrict__ X, const int*
   }
 }
 
+// gnu[c] += -(Lift z, Lift z_adj)_K for the forward state (f, lam) and the
+// adjoint state (fa, lama) of every cell of the batch.
+__global__ void k_gradnu(QuadTables Q, const double* __restrict__ X, const int* __restrict__ cells,
+                         int c0, int nbatch, const double* __restrict__ nu, int nu_per_cell, double beta,
+                         const double* __restrict__ f, const double* __restrict__ lam,
+                         const double* __restrict__ fa, const double* __restrict__ lama, int m,
+                         const int* __restrict__ cell_dofs, double* ws, double* gnu, int* status) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nbatch) return;
+  int c = c0 + t;
+  CellGeom g;
+  cell_geom(X, cells + 3 * c, g);
+  double lk[6 * (KMAX + 1)], la[6 * (KMAX + 1)];
+  for (int i = 0; i < 3; ++i) {
+    int d = cell_dofs[3 * c + i];
+    for (int cc = 0; cc < 2; ++cc)
+      for (int j = 0; j < m; ++j) {
+        const long gi = ((long)d * 2 + cc) * m + j;
+        lk[(i * 2 + cc) * m + j] = d >= 0 ? lam[gi] : 0.0;
+        la[(i * 2 + cc) * m + j] = d >= 0 ? lama[gi] : 0.0;
+      }
+  }
+  double out[1];
+  double nuc = nu_per_cell ? nu[c] : nu[0];
+  int rc = element_local(Q, g, nuc, beta, 0.0, EL_GRADNU, f + (long)c * Q.nq * 2, lk, 0.0, WS{ws + t, nbatch},
+                         out, fa + (long)c * Q.nq * 2, la);
+  if (rc) atomicOr(status, 1);
+  gnu[c] += out[0];
+}
+
+// out = in * (w_q |K|) (inverse = 0) or in / (w_q |K|) (inverse = 1) for
+// [n_cells][n_q][2] data-point arrays (w_q: the data rule's weights on the
+// reference cell, normalised to sum 1).
+__global__ void k_data_weight(QuadTables Q, const double* __restrict__ X, const int* __restrict__ cells, int nc,
+                              const double* in, int inverse, double* out) {  // in may equal out
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)nc * Q.nq) return;
+  const long c = t / Q.nq;
+  const int q = (int)(t % Q.nq);
+  const int* v = cells + 3 * c;
+  const double ax = X[2 * v[1]] - X[2 * v[0]], ay = X[2 * v[1] + 1] - X[2 * v[0] + 1];
+  const double bx = X[2 * v[2]] - X[2 * v[0]], by = X[2 * v[2] + 1] - X[2 * v[0] + 1];
+  const double w = Q.wq[q] * 0.5 * fabs(ax * by - ay * bx);
+  const double s = inverse ? 1.0 / w : w;
+  out[2 * t] = in[2 * t] * s;
+  out[2 * t + 1] = in[2 * t + 1] * s;
+}
+
 __global__ void k_cr_blocks(const double* __restrict__ X, const int* __restrict__ cells, int nc,
                             const double* __restrict__ nu_cells, double beta, double eps_inv,
                             double* A) {
@@ -412,6 +460,18 @@ void launch_recover(hipStream_t st, const QuadTables& Q, const double* X, const 
                     double* u, double* p, int* status) {
   hipLaunchKernelGGL(k_recover, dim3(nblk(nbatch, 64)), dim3(64), 0, st, Q, X, cells, c0, nbatch, nu,
                      nu_per_cell, beta, f, lam, p0, m, cell_dofs, ws, u, p, status);
+}
+void launch_gradnu(hipStream_t st, const QuadTables& Q, const double* X, const int* cells, int c0, int nbatch,
+                   const double* nu, int nu_per_cell, double beta, const double* f, const double* lam,
+                   const double* fa, const double* lama, int m, const int* cell_dofs, double* ws, double* gnu,
+                   int* status) {
+  hipLaunchKernelGGL(k_gradnu, dim3(nblk(nbatch, 64)), dim3(64), 0, st, Q, X, cells, c0, nbatch, nu,
+                     nu_per_cell, beta, f, lam, fa, lama, m, cell_dofs, ws, gnu, status);
+}
+void launch_data_weight(hipStream_t st, const QuadTables& Q, const double* X, const int* cells, int nc,
+                        const double* in, int inverse, double* out) {
+  const long n = (long)nc * Q.nq;
+  if (n > 0) hipLaunchKernelGGL(k_data_weight, dim3(nblk(n)), dim3(TPB), 0, st, Q, X, cells, nc, in, inverse, out);
 }
 void launch_cr_blocks(hipStream_t st, const double* X, const int* cells, int nc, const double* nu_cells,
                       double beta, double eps_inv, double* A) {

@@ -37,6 +37,15 @@ void launch_recover(hipStream_t st, const QuadTables& Q, const double* X, const 
                     int c0, int nbatch, const double* nu, int nu_per_cell, double beta,
                     const double* f, const double* lam, const double* p0, int m,
                     const int* cell_dofs, double* ws, double* u, double* p, int* status);
+// gnu[c] += -(Lift z, Lift z_adj)_K for cells c0 .. c0+nbatch (forward
+// source f and skeleton vector lam, adjoint source fa and skeleton vector lama).
+void launch_gradnu(hipStream_t st, const QuadTables& Q, const double* X, const int* cells, int c0, int nbatch,
+                   const double* nu, int nu_per_cell, double beta, const double* f, const double* lam,
+                   const double* fa, const double* lama, int m, const int* cell_dofs, double* ws, double* gnu,
+                   int* status);
+// out = in * (w_q |K|), or in / (w_q |K|) when inverse != 0, on [nc][nq][2].
+void launch_data_weight(hipStream_t st, const QuadTables& Q, const double* X, const int* cells, int nc,
+                        const double* in, int inverse, double* out);
 void launch_cr_blocks(hipStream_t st, const double* X, const int* cells, int nc,
                       const double* nu_cells, double beta, double eps_inv, double* A);
 void launch_patch_inverse(hipStream_t st, LevelView L, const int* pc_ptr, const int* pc,

@@ -160,6 +160,10 @@ struct hdgmg_ctx {
   double *fdiv = nullptr, *cdiv = nullptr, *area = nullptr;
   double* gK = nullptr;
   double* statebuf = nullptr;  // [N_skel + n_cells] for hdgmg_solve without state
+  // adjoint solve buffers (allocated at the first hdgmg_solve_adjoint)
+  double* adj_f = nullptr;      // [n_cells][n_q][2] adjoint source values
+  double* adj_p = nullptr;      // [n_cells][n_q] adjoint pressure
+  double* adj_state = nullptr;  // [N_skel + n_cells]
   double* ws = nullptr;
   size_t ws_bytes = 0;
   int* status = nullptr;
@@ -872,7 +876,8 @@ hdgmg_status build_coarse(hdgmg_ctx* ctx) {
 }
 
 hdgmg_status batched(hdgmg_ctx* ctx, int nc, int k, int mode, const double* f, const double* lam,
-                     const double* p0, double* out1, double* out2) {
+                     const double* p0, double* out1, double* out2, const double* f2 = nullptr,
+                     const double* lam2 = nullptr) {
   long per = element_ws_size(k);
   long batch = std::max<long>(1, std::min<long>(nc, (long)(ctx->ws_bytes / (per * sizeof(double)))));
   HIPC(hipMemsetAsync(ctx->status, 0, sizeof(int), ctx->st));
@@ -885,12 +890,18 @@ hdgmg_status batched(hdgmg_ctx* ctx, int nc, int k, int mode, const double* f, c
     else if (mode == EL_LOAD)
       launch_load(ctx->st, ctx->Q, D.X, D.cells, (int)c0, nb, D.nu, 1, ctx->beta, f, ctx->ws, out1,
                   ctx->status);
+    else if (mode == EL_GRADNU)
+      launch_gradnu(ctx->st, ctx->Q, D.X, D.cells, (int)c0, nb, D.nu, 1, ctx->beta, f, lam, f2, lam2, D.m,
+                    D.cell_dofs, ctx->ws, out1, ctx->status);
     else
       launch_recover(ctx->st, ctx->Q, D.X, D.cells, (int)c0, nb, D.nu, 1, ctx->beta, f, lam, p0, D.m,
                      D.cell_dofs, ctx->ws, out1, out2, ctx->status);
     HIPC(hipGetLastError());
   }
-  return check_status(ctx, mode == EL_CONDENSE ? "condensation" : mode == EL_LOAD ? "load" : "recovery");
+  return check_status(ctx, mode == EL_CONDENSE ? "condensation"
+                           : mode == EL_LOAD   ? "load"
+                           : mode == EL_GRADNU ? "viscosity gradient"
+                                               : "recovery");
 }
 
 }  // namespace
@@ -1238,6 +1249,34 @@ hdgmg_status hdgmg_solve(hdgmg_ctx* ctx, const double* f_qp, double* u_qp, doubl
   }
   TRY(hdgmg_recover(ctx, f_qp, stt, u_qp, p_qp));
   HIPC(hipStreamSynchronize(st));
+  return result;
+}
+
+hdgmg_status hdgmg_solve_adjoint(hdgmg_ctx* ctx, const double* f_qp, const double* state, const double* gu_qp,
+                                 double* gf_qp, double* gnu, double* adj_state, hdgmg_info* info) {
+  if (!ctx || !f_qp || !state || !gu_qp || !gf_qp) return HDGMG_EINVAL;
+  if (!ctx->assembled) {
+    ctx->err = "hdgmg_solve_adjoint before hdgmg_assemble";
+    return HDGMG_ESTATE;
+  }
+  const DevLevel& KL = ctx->K;
+  const long nqd = (long)KL.nc * ctx->Q.nq;
+  if (!ctx->adj_f) {
+    TRY(dalloc(ctx, &ctx->adj_f, (size_t)nqd * 2));
+    TRY(dalloc(ctx, &ctx->adj_p, (size_t)nqd));
+    TRY(dalloc(ctx, &ctx->adj_state, (size_t)(KL.ndof + KL.nc)));
+  }
+  double* ast = adj_state ? adj_state : ctx->adj_state;
+  // the adjoint load v -> sum gu . v(x_q) is the forward load of gu / (w_q |K|)
+  launch_data_weight(ctx->st, ctx->Q, KL.X, KL.cells, KL.nc, gu_qp, 1, ctx->adj_f);
+  HIPC(hipGetLastError());
+  hdgmg_status result = hdgmg_solve(ctx, ctx->adj_f, gf_qp, ctx->adj_p, ast, info);
+  if (result < 0) return result;
+  // dJ/df = w_q |K| u_adj(x_q)
+  launch_data_weight(ctx->st, ctx->Q, KL.X, KL.cells, KL.nc, gf_qp, 0, gf_qp);
+  HIPC(hipGetLastError());
+  if (gnu) TRY(batched(ctx, KL.nc, ctx->k, EL_GRADNU, f_qp, state, nullptr, gnu, nullptr, ctx->adj_f, ast));
+  HIPC(hipStreamSynchronize(ctx->st));
   return result;
 }
 
