@@ -39,3 +39,40 @@ def source(X, nu, beta):
     u = velocity(X)
     gp = np.stack([(1 - 2 * x) * (1 - y), -x * (1 - x)], axis=-1)
     return -nu * np.stack([lap_ux, lap_uy], axis=-1) + beta * u + gp
+
+
+# Cavity-type solution with a tangential boundary velocity on the top side:
+# u = curl(psi), psi = g(x) h(y), h(y) = y^2 (1 - y), so u.n = 0 on the whole
+# boundary, u = 0 on the left, right and bottom sides and u_x = -g(x) on top.
+def h0(t): return t ** 2 - t ** 3
+def h1(t): return 2 * t - 3 * t ** 2
+def h2(t): return 2 - 6 * t
+def h3(t): return -6.0 + 0 * t
+
+
+def cavity_velocity(X):
+    x, y = X[..., 0], X[..., 1]
+    return np.stack([g0(x) * h1(y), -g1(x) * h0(y)], axis=-1)
+
+
+def cavity_grad_velocity(X):
+    """[..., i, j] = d u_i / d x_j."""
+    x, y = X[..., 0], X[..., 1]
+    G = np.zeros(X.shape[:-1] + (2, 2))
+    G[..., 0, 0] = g1(x) * h1(y)
+    G[..., 0, 1] = g0(x) * h2(y)
+    G[..., 1, 0] = -g2(x) * h0(y)
+    G[..., 1, 1] = -g1(x) * h1(y)
+    return G
+
+
+def cavity_source(X, nu, beta, wind_scale):
+    """-nu Lap u + beta u + (w . grad) u + grad p with w = wind_scale * u
+    and the pressure of `pressure`."""
+    x, y = X[..., 0], X[..., 1]
+    lap = np.stack([g2(x) * h1(y) + g0(x) * h3(y), -(g3(x) * h0(y) + g1(x) * h2(y))], axis=-1)
+    u = cavity_velocity(X)
+    G = cavity_grad_velocity(X)
+    conv = wind_scale * np.einsum("...ij,...j->...i", G, u)
+    gp = np.stack([(1 - 2 * x) * (1 - y), -x * (1 - x)], axis=-1)
+    return -nu * lap + beta * u + conv + gp
