@@ -97,11 +97,19 @@ typedef struct {
   int vcycle_precision;    /* storage of every operator the preconditioner
                               reads: 0 FP64, 1 FP32 (vectors, accumulation
                               and the outer Krylov solver stay FP64)       */
+  int oseen;               /* 1: the context solves Picard-linearised
+                              (Oseen) systems (Sec. 4): hdgmg_set_wind is
+                              allowed, every block and patch factor is
+                              stored and inverted as nonsymmetric, and the
+                              inner solver is FGMRES(restart) with right
+                              preconditioning; 0: generalized Stokes with
+                              flexible CG                                   */
+  int restart;             /* FGMRES restart length, 1..64                  */
 } hdgmg_opts;
 
 /* Defaults: m_p = m_h = 1, V-cycle, growth 2, rtol 1e-8, atol 1e-10,
  * max_it 500, uzawa_max 50, uzawa_tol 1e-10, coarse_dofs 2048,
- * stream_dofs 200000, vcycle_precision 0. */
+ * stream_dofs 200000, vcycle_precision 0, oseen 0, restart 50. */
 void hdgmg_default_opts(hdgmg_opts* opts);
 
 #define HDGMG_MAX_UZAWA 64
@@ -169,10 +177,42 @@ hdgmg_status hdgmg_solve(hdgmg_ctx* ctx, const double* f_qp, double* u_qp,
  * The adjoint state solves the forward system (same AL-Uzawa, flexible CG
  * and MG_hp) with the load v -> sum_{K,q} gu_qp . v(x_q).  gf_qp must not
  * alias the inputs.  Returns as hdgmg_solve; outputs are undefined on a
- * negative status. */
+ * negative status.  ESTATE while a wind or Dirichlet data are set (the
+ * adjoint of the nonsymmetric and inhomogeneous cases is not provided). */
 hdgmg_status hdgmg_solve_adjoint(hdgmg_ctx* ctx, const double* f_qp, const double* state,
                                  const double* gu_qp, double* gf_qp, double* gnu,
                                  double* adj_state, hdgmg_info* info);
+
+/* hdgmg_solve from an initial skeleton iterate: x0 (device, N_skel, may be
+ * NULL for zero) starts the first inner solve of the AL-Uzawa iteration;
+ * for Picard steps (Sec. 4.2) it is the previous step's skeleton vector
+ * (state[0 .. N_skel)).  With opts.oseen every later inner solve starts
+ * from the latest iterate; the Stokes path starts every inner solve from
+ * zero.  x0 may alias state. */
+hdgmg_status hdgmg_solve_x0(hdgmg_ctx* ctx, const double* f_qp, const double* x0,
+                            double* u_qp, double* p_qp, double* state, hdgmg_info* info);
+
+/* Wind of the Picard-linearised convection (Sec. 4.2: the previous
+ * velocity), given by its values at the data points, w_qp device
+ * [n_cells][n_q][2] (for instance u_qp of a previous solve), or NULL for no
+ * convection.  The field must be a discrete velocity of the scheme (RT_k in
+ * every cell, normal-continuous, zero normal component on the boundary):
+ * its RT_k coefficients are recovered exactly by the data-rule L^2
+ * projection.  Its facet fluxes define the lowest-order winds of MG_h (the
+ * RT0 field with the same fluxes on the finest level, and on each coarser
+ * level the sums over the two halves of every facet).  Requires
+ * opts.oseen; takes effect at the next hdgmg_assemble (the context is
+ * unassembled until then).  Returns ESTATE without opts.oseen, ENONFINITE
+ * for a degenerate fit. */
+hdgmg_status hdgmg_set_wind(hdgmg_ctx* ctx, const double* w_qp);
+
+/* Tangential Dirichlet data on the boundary facets (the lid of a cavity):
+ * uhat_b device [n_boundary_facets][k+1], per boundary facet (in facet
+ * order, see hdgmg_export what 3) the coefficients of uhat . t_F in the
+ * facet Legendre basis; NULL restores homogeneous data.  The normal
+ * component stays zero.  The data enter the condensed load (hdgmg_rhs, as
+ * -S_K lambda_b) and the recovery; the array is read during the call. */
+hdgmg_status hdgmg_set_dirichlet(hdgmg_ctx* ctx, const double* uhat_b);
 
 /* Condensed load g (length N_skel, device, output) of f_qp (device), the
  * right-hand side F_{k,h} of stOptForm. */
@@ -201,7 +241,8 @@ hdgmg_status hdgmg_recover(hdgmg_ctx* ctx, const double* f_qp,
 /* Sizes.  what: 0 n_cells (finest), 1 n_q, 2 N_skel, 3 levels J,
  * 4 device bytes held, 5 n_interior_facets (finest), 6 k,
  * 7 n_colours (finest level), 8 n_cells of level `level`,
- * 9 N of the lowest-order space of level `level` (2 n_interior_facets).
+ * 9 N of the lowest-order space of level `level` (2 n_interior_facets),
+ * 10 n_boundary_facets (finest).
  * level counts from 0 (coarsest) and is ignored by 0..7. */
 hdgmg_status hdgmg_query(const hdgmg_ctx* ctx, int what, int level, int64_t* value);
 
@@ -211,6 +252,9 @@ hdgmg_status hdgmg_query(const hdgmg_ctx* ctx, int what, int level, int64_t* val
  *           [n_cells(level)][6][6]
  *   what 2: coordinates of the data points of the finest cells
  *           [n_cells][n_q][2]
+ *   what 3: end points of the finest boundary facets, in facet order,
+ *           [n_boundary_facets][2][2] (vertex v0 < v1 first: t_F points
+ *           from the first to the second)
  * Local DOF order inside a block: (local facet i, component c, mode j) ->
  * (i*2 + c)*m + j, local facet i opposite the cell's i-th stored vertex.
  * `bytes` is the size of dst; EINVAL if too small. */

@@ -30,7 +30,8 @@ class Opts(ctypes.Structure):
                 ("vcycle_growth", ctypes.c_int), ("rtol", ctypes.c_double),
                 ("atol", ctypes.c_double), ("max_it", ctypes.c_int), ("uzawa_max", ctypes.c_int),
                 ("uzawa_tol", ctypes.c_double), ("coarse_dofs", ctypes.c_int),
-                ("stream_dofs", ctypes.c_int), ("vcycle_precision", ctypes.c_int)]
+                ("stream_dofs", ctypes.c_int), ("vcycle_precision", ctypes.c_int),
+                ("oseen", ctypes.c_int), ("restart", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -45,7 +46,7 @@ class HdgmgError(RuntimeError):
 
 
 SYMBOLS = ["hdgmg_default_opts", "hdgmg_setup", "hdgmg_assemble", "hdgmg_solve",
-           "hdgmg_solve_adjoint", "hdgmg_rhs",
+           "hdgmg_solve_adjoint", "hdgmg_solve_x0", "hdgmg_set_wind", "hdgmg_set_dirichlet", "hdgmg_rhs",
            "hdgmg_apply", "hdgmg_precondition", "hdgmg_inner_solve", "hdgmg_recover",
            "hdgmg_query", "hdgmg_export", "hdgmg_kernel_timer", "hdgmg_kernel_timer_read",
            "hdgmg_last_error", "hdgmg_destroy"]
@@ -71,6 +72,11 @@ def lib():
     L.hdgmg_solve.restype = i32
     L.hdgmg_solve_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(Info)]
     L.hdgmg_solve_adjoint.restype = i32
+    L.hdgmg_solve_x0.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(Info)]
+    L.hdgmg_solve_x0.restype = i32
+    for name in ("hdgmg_set_wind", "hdgmg_set_dirichlet"):
+        getattr(L, name).argtypes = [vp, vp]
+        getattr(L, name).restype = i32
     for name in ("hdgmg_rhs", "hdgmg_apply", "hdgmg_precondition"):
         getattr(L, name).argtypes = [vp, vp, vp]
         getattr(L, name).restype = i32
@@ -198,14 +204,16 @@ class Solver:
         self._check(lib().hdgmg_recover(self._h, _ptr(f_qp), _ptr(state), _ptr(u), _ptr(p)))
         return u, p
 
-    def solve(self, f_qp):
-        """Returns (u_qp, p_qp, state, info dict, status)."""
+    def solve(self, f_qp, x0=None):
+        """Returns (u_qp, p_qp, state, info dict, status).  x0: initial
+        skeleton iterate (N_skel), e.g. state[:n_skel] of a previous solve."""
         u = self.torch.empty((self.n_cells, self.n_q, 2), dtype=self.torch.float64, device="cuda")
         p = self.torch.empty((self.n_cells, self.n_q), dtype=self.torch.float64, device="cuda")
         state = self._vec(self.n_skel + self.n_cells)
         info = Info()
-        st = self._check(lib().hdgmg_solve(self._h, _ptr(f_qp), _ptr(u), _ptr(p), _ptr(state),
-                                           ctypes.byref(info)), allow=(0, 1))
+        x0p = ctypes.c_void_p(None) if x0 is None else _ptr(x0)
+        st = self._check(lib().hdgmg_solve_x0(self._h, _ptr(f_qp), x0p, _ptr(u), _ptr(p), _ptr(state),
+                                              ctypes.byref(info)), allow=(0, 1))
         n = info.uzawa_steps
         d = dict(uzawa_steps=n, its=list(info.its[:n]), rel_res=list(info.rel_res[:n]),
                  dp_l2=list(info.dp_l2[:n]))
@@ -229,6 +237,35 @@ class Solver:
         d = dict(uzawa_steps=n, its=list(info.its[:n]), rel_res=list(info.rel_res[:n]),
                  dp_l2=list(info.dp_l2[:n]))
         return gf, gnu, adj_state, d, st
+
+    def set_wind(self, w_qp):
+        """Picard wind at the data points [n_cells][n_q][2] (None: no
+        convection); re-assemble afterwards."""
+        self._check(lib().hdgmg_set_wind(self._h, ctypes.c_void_p(None) if w_qp is None else _ptr(w_qp)))
+
+    def set_dirichlet(self, uhat_b):
+        """Tangential boundary coefficients [n_boundary_facets][k+1] (None:
+        homogeneous)."""
+        self._check(lib().hdgmg_set_dirichlet(self._h, ctypes.c_void_p(None) if uhat_b is None else _ptr(uhat_b)))
+
+    def boundary_facets(self):
+        """End points [n_boundary_facets][2][2] of the boundary facets (facet order)."""
+        nb = self.query(10)
+        out = self.torch.empty((max(nb, 1), 2, 2), dtype=self.torch.float64, device="cuda")
+        self._check(lib().hdgmg_export(self._h, 3, 0, _ptr(out), out.numel() * 8))
+        return out[:nb]
+
+    def lid_data(self, top=1.0):
+        """uhat = (1, 0) on the boundary facets of the side y = top (mode 0
+        = (1, 0) . t_F), zero elsewhere: [n_boundary_facets][k+1]."""
+        t = self.torch
+        e = self.boundary_facets()
+        d = e[:, 1] - e[:, 0]
+        tx = d[:, 0] / t.linalg.norm(d, dim=1)
+        on = (e[:, 0, 1] - top).abs().lt(1e-12) & (e[:, 1, 1] - top).abs().lt(1e-12)
+        out = t.zeros((e.shape[0], self.k + 1), dtype=t.float64, device="cuda")
+        out[:, 0] = t.where(on, tx, t.zeros_like(tx))
+        return out
 
     def timer(self, kernel_class, enable=True):
         """Enable/disable the live event timer of a kernel class (see hdgmg.h)."""
@@ -302,3 +339,24 @@ def stokes_solve(solver, f_qp, nu):
     if _STOKES_SOLVE is None:
         _STOKES_SOLVE = _make_function()
     return _STOKES_SOLVE.apply(solver, f_qp, nu)
+
+
+def picard(solver, f_qp, steps, dirichlet=None):
+    """Stokes solve then `steps` Picard steps (Sec. 4.2) on an opts.oseen
+    Solver: each step takes the previous velocity as the wind and the
+    previous skeleton vector as the initial iterate.  Returns the list of
+    (u_qp, p_qp, state, info, status) per solve."""
+    if dirichlet is not None:
+        solver.set_dirichlet(dirichlet)
+    solver.set_wind(None)
+    solver.assemble()
+    out = []
+    x0 = None
+    for n in range(steps + 1):
+        if n > 0:
+            solver.set_wind(out[-1][0])
+            solver.assemble()
+        u, p, state, info, st = solver.solve(f_qp, x0=x0)
+        out.append((u, p, state, info, st))
+        x0 = state[:solver.n_skel]
+    return out

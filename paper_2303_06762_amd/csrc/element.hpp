@@ -45,6 +45,20 @@ struct QuadTables {
   double ws[NF_MAX];     // weights, sum 1
 };
 
+// Rules of the convection terms (Sec. 4.1) for a discrete wind in RT_k:
+// the volume and facet integrands have degree 3k+2, so the Stroud rule and
+// Gauss-Legendre with n = floor((3k+4)/2) points per direction are exact.
+// The upwind switch is taken at the facet points.  Kept in device memory
+// (passed by pointer).
+constexpr int NC_MAX = (3 * KMAX + 4) / 2;
+struct ConvTables {
+  int n, nq;
+  double xi[NC_MAX * NC_MAX][2];
+  double wq[NC_MAX * NC_MAX];  // sum 1
+  double s[NC_MAX];
+  double ws[NC_MAX];           // sum 1
+};
+
 struct Dims {
   int k, m, nP, na, nz, nK, nN, nD, nkkt, ntop;
 };
@@ -236,10 +250,20 @@ enum { EL_CONDENSE = 0, EL_LOAD = 1, EL_RECOVER = 2, EL_GRADNU = 3 };
 //                -(Lift(z), Lift(z2))_K, the derivative with respect to this
 //                cell's viscosity of the adjoint-weighted residual (the only
 //                nu-dependent term of the element energy is nu ||Lift||^2)
+// With a wind (CT and wc non-null; wc = the wind's coefficients in this
+// cell's RT_k basis) the element matrix gains the Picard convection form of
+// Sec. 4.1 (test v, trial u):
+//   - sum_ij (u_i w_j, d_j v_i)_K + <(w.n_K) t(u_up), t(v) - vhat>_{dK},
+// with u_up the cell's own trace where w.n_K > 0 and uhat where w.n_K < 0;
+// the volume terms then use the convection rule and the source term the
+// data rule.  H is nonsymmetric; rows are test functions, so the condensed
+// rows of tangential unknowns read H_ta (rows), not H_at^T, and S is not
+// symmetrised.
 HDI int element_local(const QuadTables& Q, const CellGeom& g, double nu, double beta,
                       double eps_inv, int mode, const double* f, const double* lam,
                       double p0, WS w, double* out, const double* f2 = nullptr,
-                      const double* lam2 = nullptr) {
+                      const double* lam2 = nullptr, const ConvTables* CT = nullptr,
+                      const double* wc = nullptr) {
   const Dims D = dims_of(Q.k);
   const int nP = D.nP, na = D.na, nz = D.nz, m = D.m, nK = D.nK, nN = D.nN, nkkt = D.nkkt;
   long o = 0;
@@ -274,12 +298,14 @@ HDI int element_local(const QuadTables& Q, const CellGeom& g, double nu, double 
   for (int i = 0; i < nP; ++i) mean[i] = 0.0;
 
   double u[2 * 40], gr[4 * 40], mono[16];
-  // ---- volume terms
-  for (int q = 0; q < Q.nq; ++q) {
-    double x1 = Q.xi[q][0], x2 = Q.xi[q][1];
+  const bool conv = CT != nullptr && wc != nullptr;
+  // ---- volume terms (the source term inline only with the data rule)
+  const int nvq = conv ? CT->nq : Q.nq;
+  for (int q = 0; q < nvq; ++q) {
+    double x1 = conv ? CT->xi[q][0] : Q.xi[q][0], x2 = conv ? CT->xi[q][1] : Q.xi[q][1];
     double xp[2] = {g.Xs0[0] + g.J[0][0] * x1 + g.J[0][1] * x2,
                     g.Xs0[1] + g.J[1][0] * x1 + g.J[1][1] * x2};
-    double wt = Q.wq[q] * g.area;
+    double wt = (conv ? CT->wq[q] : Q.wq[q]) * g.area;
     rt_basis(D, g, x1, x2, xp, u, gr, mono);
     for (int r = 0; r < nP; ++r) {
       mean[r] += wt * mono[r];
@@ -294,12 +320,42 @@ HDI int element_local(const QuadTables& Q, const CellGeom& g, double nu, double 
       }
       for (int b = 0; b <= a; ++b)
         H[(long)a * nz + b] += beta * wt * (u[2 * a] * u[2 * b] + u[2 * a + 1] * u[2 * b + 1]);
-      if (mode != EL_CONDENSE) F[a] += wt * (f[2 * q] * u[2 * a] + f[2 * q + 1] * u[2 * a + 1]);
-      if (mode == EL_GRADNU) F[na + a] += wt * (f2[2 * q] * u[2 * a] + f2[2 * q + 1] * u[2 * a + 1]);
+      if (!conv && mode != EL_CONDENSE) F[a] += wt * (f[2 * q] * u[2 * a] + f[2 * q + 1] * u[2 * a + 1]);
+      if (!conv && mode == EL_GRADNU) F[na + a] += wt * (f2[2 * q] * u[2 * a] + f2[2 * q + 1] * u[2 * a + 1]);
     }
   }
   for (int a = 0; a < na; ++a)
     for (int b = 0; b < a; ++b) H[(long)b * nz + a] = H[(long)a * nz + b];
+  if (conv) {
+    // source term with the data rule
+    if (mode != EL_CONDENSE)
+      for (int q = 0; q < Q.nq; ++q) {
+        double x1 = Q.xi[q][0], x2 = Q.xi[q][1];
+        double xp[2] = {g.Xs0[0] + g.J[0][0] * x1 + g.J[0][1] * x2,
+                        g.Xs0[1] + g.J[1][0] * x1 + g.J[1][1] * x2};
+        double wt = Q.wq[q] * g.area;
+        rt_basis(D, g, x1, x2, xp, u, gr, mono);
+        for (int a = 0; a < na; ++a) F[a] += wt * (f[2 * q] * u[2 * a] + f[2 * q + 1] * u[2 * a + 1]);
+      }
+    // - sum_ij (u_i w_j, d_j v_i): H[test b][trial a]
+    for (int q = 0; q < CT->nq; ++q) {
+      double x1 = CT->xi[q][0], x2 = CT->xi[q][1];
+      double xp[2] = {g.Xs0[0] + g.J[0][0] * x1 + g.J[0][1] * x2,
+                      g.Xs0[1] + g.J[1][0] * x1 + g.J[1][1] * x2};
+      double wt = CT->wq[q] * g.area;
+      rt_basis(D, g, x1, x2, xp, u, gr, mono);
+      double wx = 0.0, wy = 0.0;
+      for (int c = 0; c < na; ++c) {
+        wx += wc[c] * u[2 * c];
+        wy += wc[c] * u[2 * c + 1];
+      }
+      for (int b = 0; b < na; ++b) {
+        const double g0 = wt * (wx * gr[4 * b + 0] + wy * gr[4 * b + 1]);  // w . grad v_b,0
+        const double g1 = wt * (wx * gr[4 * b + 2] + wy * gr[4 * b + 3]);  // w . grad v_b,1
+        for (int a = 0; a < na; ++a) H[(long)b * nz + a] -= g0 * u[2 * a] + g1 * u[2 * a + 1];
+      }
+    }
+  }
   for (int r = 0; r < nP; ++r) mean[r] /= g.area;
   // ---- facet terms
   double phi[KMAX + 1];
@@ -329,6 +385,43 @@ HDI int element_local(const QuadTables& Q, const CellGeom& g, double nu, double 
         for (int a = 0; a < na; ++a)
           Nm[(long)(i * m + j) * na + a] +=
               Q.ws[l] * phi[j] * (u[2 * a] * g.n[i][0] + u[2 * a + 1] * g.n[i][1]);
+    }
+  }
+  // ---- convection facet terms: <(w.n_K) t(u_up), t(v) - vhat>
+  if (conv) {
+    for (int i = 0; i < 3; ++i) {
+      const double* t = g.t[i];
+      double nK_[2] = {g.sigma[i] * g.n[i][0], g.sigma[i] * g.n[i][1]};
+      for (int l = 0; l < CT->n; ++l) {
+        double s = CT->s[l];
+        double xp[2] = {g.P0[i][0] + s * (g.P1[i][0] - g.P0[i][0]),
+                        g.P0[i][1] + s * (g.P1[i][1] - g.P0[i][1])};
+        double dx = xp[0] - g.Xs0[0], dy = xp[1] - g.Xs0[1];
+        double x1 = g.Ji[0][0] * dx + g.Ji[0][1] * dy;
+        double x2 = g.Ji[1][0] * dx + g.Ji[1][1] * dy;
+        rt_basis(D, g, x1, x2, xp, u, gr, mono);
+        facet_legendre(D.k, s, phi);
+        double wn = 0.0;
+        for (int c = 0; c < na; ++c) wn += wc[c] * (u[2 * c] * nK_[0] + u[2 * c + 1] * nK_[1]);
+        if (wn == 0.0) continue;
+        const double cw = CT->ws[l] * g.len[i] * wn;
+        // test rows: RT coefficients (v.t) and this facet's uhat modes (-phi)
+        for (int b = 0; b < nz; ++b) {
+          double tv;
+          if (b < na)
+            tv = u[2 * b] * t[0] + u[2 * b + 1] * t[1];
+          else if (b >= na + i * m && b < na + (i + 1) * m)
+            tv = -phi[b - na - i * m];
+          else
+            continue;
+          tv *= cw;
+          if (wn > 0.0) {
+            for (int a = 0; a < na; ++a) H[(long)b * nz + a] += tv * (u[2 * a] * t[0] + u[2 * a + 1] * t[1]);
+          } else {
+            for (int j = 0; j < m; ++j) H[(long)b * nz + na + i * m + j] += tv * phi[j];
+          }
+        }
+      }
     }
   }
   // ---- H += nu sum_ij R_ij^T M^-1 R_ij (Cholesky of M)
@@ -461,7 +554,7 @@ HDI int element_local(const QuadTables& Q, const CellGeom& g, double nu, double 
           btx = Bx[(long)(na + i * m + j) * ncol + cc];
         } else {
           btx = 0.0;
-          for (int a = 0; a < na; ++a) btx -= H[(long)a * nz + na + i * m + j] * Bx[(long)a * ncol + cc];
+          for (int a = 0; a < na; ++a) btx -= H[(long)(na + i * m + j) * nz + a] * Bx[(long)a * ncol + cc];
         }
         if (mode == EL_LOAD) {
           out[l1] = btx;
@@ -473,13 +566,15 @@ HDI int element_local(const QuadTables& Q, const CellGeom& g, double nu, double 
         }
       }
     }
-    if (mode == EL_CONDENSE) {
+    if (mode == EL_CONDENSE && !conv) {
       for (int a = 0; a < nK; ++a)
         for (int b = 0; b < a; ++b) {
           double s = 0.5 * (out[a * nK + b] + out[b * nK + a]);
           out[a * nK + b] = s;
           out[b * nK + a] = s;
         }
+    }
+    if (mode == EL_CONDENSE) {
       for (int i1 = 0; i1 < 3; ++i1)
         for (int i2 = 0; i2 < 3; ++i2)
           out[(i1 * 2 * m) * nK + i2 * 2 * m] +=
@@ -525,6 +620,55 @@ HDI int element_local(const QuadTables& Q, const CellGeom& g, double nu, double 
       out[2 * Q.nq + q] = p;
     }
   }
+  return 0;
+}
+
+// Coefficients in this cell's RT_k basis of a velocity field given at the
+// data points: the L^2 projection with the data rule, which is exact for a
+// field in RT_k (the products have degree <= 2k+2).  Workspace na*(na+1).
+// Returns 1 if the Gram matrix is singular.
+HDI int wind_fit(const QuadTables& Q, const CellGeom& g, const double* vals, WS w, double* coef) {
+  const Dims D = dims_of(Q.k);
+  const int na = D.na;
+  WS G{w.p, w.s};
+  WS r{w.p + (long)na * na * w.s, w.s};
+  for (long i = 0; i < (long)na * na; ++i) G[i] = 0.0;
+  for (int a = 0; a < na; ++a) r[a] = 0.0;
+  double u[2 * 40], gr[4 * 40], mono[16];
+  for (int q = 0; q < Q.nq; ++q) {
+    double x1 = Q.xi[q][0], x2 = Q.xi[q][1];
+    double xp[2] = {g.Xs0[0] + g.J[0][0] * x1 + g.J[0][1] * x2,
+                    g.Xs0[1] + g.J[1][0] * x1 + g.J[1][1] * x2};
+    double wt = Q.wq[q] * g.area;
+    rt_basis(D, g, x1, x2, xp, u, gr, mono);
+    for (int a = 0; a < na; ++a) {
+      r[a] += wt * (vals[2 * q] * u[2 * a] + vals[2 * q + 1] * u[2 * a + 1]);
+      for (int b = 0; b <= a; ++b) G[(long)a * na + b] += wt * (u[2 * a] * u[2 * b] + u[2 * a + 1] * u[2 * b + 1]);
+    }
+  }
+  for (int j = 0; j < na; ++j) {
+    double d = G[(long)j * na + j];
+    for (int p = 0; p < j; ++p) d -= G[(long)j * na + p] * G[(long)j * na + p];
+    if (!(d > 0)) return 1;
+    d = sqrt(d);
+    G[(long)j * na + j] = d;
+    for (int i = j + 1; i < na; ++i) {
+      double t = G[(long)i * na + j];
+      for (int p = 0; p < j; ++p) t -= G[(long)i * na + p] * G[(long)j * na + p];
+      G[(long)i * na + j] = t / d;
+    }
+  }
+  for (int i = 0; i < na; ++i) {
+    double t = r[i];
+    for (int p = 0; p < i; ++p) t -= G[(long)i * na + p] * r[p];
+    r[i] = t / G[(long)i * na + i];
+  }
+  for (int i = na - 1; i >= 0; --i) {
+    double t = r[i];
+    for (int p = i + 1; p < na; ++p) t -= G[(long)p * na + i] * r[p];
+    r[i] = t / G[(long)i * na + i];
+  }
+  for (int a = 0; a < na; ++a) coef[a] = r[a];
   return 0;
 }
 

@@ -169,20 +169,26 @@ __global__ void k_pack_patches(int np, int gp0, int m2, const int* __restrict__ 
 inline int nblk(long n, int t = 256) { return (int)((n + t - 1) / t); }
 
 template <typename TS>
-void cell_apply_t(hipStream_t st, int m2, int nc, const TS* Sp, const int* cdof, const double* x, double* yF) {
+void cell_apply_t(hipStream_t st, int m2, int nc, const TS* Sp, const int* cdof, const double* x, double* yF,
+                  bool full) {
+  if (!fast_cell_packed(3 * m2, full)) {
+    switch (m2) {
+#define CASE(M)                                                                                        \
+  case M:                                                                                              \
+    hipLaunchKernelGGL((k_cell_apply_rows<M, TS>), dim3((nc + 256 / (3 * M) - 1) / (256 / (3 * M))),   \
+                       dim3(256), 0, st, nc, Sp, cdof, x, yF);                                         \
+    break;
+      CASE(2) CASE(4) CASE(6) CASE(8) CASE(10)
+#undef CASE
+    }
+    return;
+  }
   switch (m2) {
 #define CASE(M)                                                                                  \
   case M:                                                                                        \
     hipLaunchKernelGGL((k_cell_apply<M, TS>), dim3(nblk(nc)), dim3(256), 0, st, nc, Sp, cdof, x, yF); \
     break;
     CASE(2) CASE(4) CASE(6)
-#undef CASE
-#define CASE(M)                                                                                        \
-  case M:                                                                                              \
-    hipLaunchKernelGGL((k_cell_apply_rows<M, TS>), dim3((nc + 256 / (3 * M) - 1) / (256 / (3 * M))),   \
-                       dim3(256), 0, st, nc, Sp, cdof, x, yF);                                         \
-    break;
-    CASE(8) CASE(10)
 #undef CASE
   }
 }
@@ -205,11 +211,13 @@ void patch_relax_t(hipStream_t st, int m2, int np, const int* pf, const TS* Pp, 
 
 template <typename TS>
 void launch_cell_apply(hipStream_t st, int m2, int nc, const TS* Sp, const int* cdof, const double* x,
-                       double* yF) {
-  if (nc > 0) cell_apply_t<TS>(st, m2, nc, Sp, cdof, x, yF);
+                       double* yF, bool full) {
+  if (nc > 0) cell_apply_t<TS>(st, m2, nc, Sp, cdof, x, yF, full);
 }
-template void launch_cell_apply<double>(hipStream_t, int, int, const double*, const int*, const double*, double*);
-template void launch_cell_apply<float>(hipStream_t, int, int, const float*, const int*, const double*, double*);
+template void launch_cell_apply<double>(hipStream_t, int, int, const double*, const int*, const double*, double*,
+                                        bool);
+template void launch_cell_apply<float>(hipStream_t, int, int, const float*, const int*, const double*, double*,
+                                       bool);
 
 void launch_facet_sum(hipStream_t st, int nint, int m2, const double* yF, const double* b, double alpha,
                       double* y) {
@@ -227,9 +235,9 @@ template void launch_patch_relax<double>(hipStream_t, int, int, const int*, cons
 template void launch_patch_relax<float>(hipStream_t, int, int, const int*, const float*, const double*,
                                         const double*, double*);
 
-void launch_pack_cells(hipStream_t st, int nc, int nK, const double* S, double* Sp) {
+void launch_pack_cells(hipStream_t st, int nc, int nK, const double* S, double* Sp, bool full) {
   if (nc <= 0) return;
-  if (nK <= 18)
+  if (fast_cell_packed(nK, full))
     hipLaunchKernelGGL(k_pack_cells<double>, dim3(nblk(nc)), dim3(256), 0, st, nc, nK, S, Sp);
   else
     hipLaunchKernelGGL(k_pack_cells_full<double>, dim3(nblk(nc)), dim3(256), 0, st, nc, nK, S, Sp);

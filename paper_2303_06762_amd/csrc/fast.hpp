@@ -11,14 +11,18 @@ namespace hdgmg {
 constexpr int FAST_NF = 6;
 
 // Cell-block storage of the streaming layout: packed upper triangle for
-// blocks up to 18 x 18 (k <= 2), full otherwise.
-inline long fast_cell_words(int nK) { return nK <= 18 ? (long)nK * (nK + 1) / 2 : (long)nK * nK; }
+// symmetric blocks up to 18 x 18 (k <= 2), full otherwise (full = true for
+// the nonsymmetric blocks of the Oseen operator).
+inline bool fast_cell_packed(int nK, bool full) { return nK <= 18 && !full; }
+inline long fast_cell_words(int nK, bool full = false) {
+  return fast_cell_packed(nK, full) ? (long)nK * (nK + 1) / 2 : (long)nK * nK;
+}
 
 // y_F[(2F+side)*m2 + c] = rows of S_K x_K for every cell K (m2 = 2 modes
 // per facet component x 2 components).
 template <typename TS>
 void launch_cell_apply(hipStream_t st, int m2, int nc, const TS* Sp, const int* cdof, const double* x,
-                       double* yF);
+                       double* yF, bool full = false);
 // y = b + alpha * (y_F[side 0] + y_F[side 1]) (b may be null)
 void launch_facet_sum(hipStream_t st, int nint, int m2, const double* yF, const double* b, double alpha,
                       double* y);
@@ -26,7 +30,7 @@ void launch_facet_sum(hipStream_t st, int nint, int m2, const double* yF, const 
 template <typename TS>
 void launch_patch_relax(hipStream_t st, int m2, int np, const int* pf, const TS* Pp, const double* b,
                         const double* yF, double* x);
-void launch_pack_cells(hipStream_t st, int nc, int nK, const double* S, double* Sp);
+void launch_pack_cells(hipStream_t st, int nc, int nK, const double* S, double* Sp, bool full = false);
 void launch_pack_patches(hipStream_t st, int np, int gp0, int m2, const int* pf_ptr, const long* pinv_off,
                          const double* pinv, double* Pp);
 

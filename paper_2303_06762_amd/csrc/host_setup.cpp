@@ -133,6 +133,32 @@ QuadTables make_tables(int k) {
   return Q;
 }
 
+ConvTables make_conv_tables(int k) {
+  ConvTables T;
+  std::memset(&T, 0, sizeof(T));
+  const int n = (3 * k + 4) / 2;
+  T.n = n;
+  T.nq = n * n;
+  double u[NC_MAX], wu[NC_MAX], v[NC_MAX], wv[NC_MAX];
+  gauss_legendre01(n, u, wu);
+  gauss_jacobi10_01(n, v, wv);
+  double tot = 0.0;
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) {
+      int q = j * n + i;
+      T.xi[q][0] = u[i] * (1.0 - v[j]);
+      T.xi[q][1] = v[j];
+      T.wq[q] = wu[i] * wv[j];
+      tot += T.wq[q];
+    }
+  for (int q = 0; q < T.nq; ++q) T.wq[q] /= tot;
+  for (int i = 0; i < n; ++i) {
+    T.s[i] = u[i];
+    T.ws[i] = wu[i];
+  }
+  return T;
+}
+
 // ------------------------------------------------------------ dense helpers
 bool invert_spd(const std::vector<double>& A, int n, std::vector<double>& inv) {
   // Cholesky then column solves; inv column-major (symmetric anyway)
@@ -167,6 +193,46 @@ bool invert_spd(const std::vector<double>& A, int n, std::vector<double>& inv) {
   return true;
 }
 
+bool invert_general(const std::vector<double>& A, int n, std::vector<double>& inv) {
+  std::vector<double> LU(A);
+  std::vector<int> piv(n);
+  for (int j = 0; j < n; ++j) {
+    int pr = j;
+    double best = std::fabs(LU[(size_t)j * n + j]);
+    for (int i = j + 1; i < n; ++i)
+      if (std::fabs(LU[(size_t)i * n + j]) > best) {
+        best = std::fabs(LU[(size_t)i * n + j]);
+        pr = i;
+      }
+    if (!(best > 0)) return false;
+    piv[j] = pr;
+    if (pr != j)
+      for (int c = 0; c < n; ++c) std::swap(LU[(size_t)j * n + c], LU[(size_t)pr * n + c]);
+    for (int i = j + 1; i < n; ++i) {
+      double l = LU[(size_t)i * n + j] / LU[(size_t)j * n + j];
+      LU[(size_t)i * n + j] = l;
+      if (l != 0.0)
+        for (int c = j + 1; c < n; ++c) LU[(size_t)i * n + c] -= l * LU[(size_t)j * n + c];
+    }
+  }
+  inv.assign((size_t)n * n, 0.0);
+  std::vector<double> col(n);
+  for (int c = 0; c < n; ++c) {
+    for (int i = 0; i < n; ++i) col[i] = i == c ? 1.0 : 0.0;
+    for (int j = 0; j < n; ++j)
+      if (piv[j] != j) std::swap(col[j], col[piv[j]]);
+    for (int i = 0; i < n; ++i)
+      for (int q = 0; q < i; ++q) col[i] -= LU[(size_t)i * n + q] * col[q];
+    for (int i = n - 1; i >= 0; --i) {
+      double t = col[i];
+      for (int q = i + 1; q < n; ++q) t -= LU[(size_t)i * n + q] * col[q];
+      col[i] = t / LU[(size_t)i * n + i];
+    }
+    for (int i = 0; i < n; ++i) inv[(size_t)c * n + i] = col[i];
+  }
+  return true;
+}
+
 void host_cr_blocks(const Level& L, const std::vector<double>& nu, double beta, double eps_inv,
                     std::vector<double>& B) {
   B.resize((size_t)L.nc * 36);
@@ -190,11 +256,9 @@ void level_viscosities(const std::vector<Level>& lv, const std::vector<double>& 
   }
 }
 
-bool stabilised_transfer(const Level& Cl, const Level& Fl, const Averaging& Av,
-                         const std::vector<double>& nu_f, double beta, double eps_inv, CSR& Pc, CSR& Rc) {
-  std::vector<double> B;
-  host_cr_blocks(Fl, nu_f, beta, eps_inv, B);
-  const int nfd = 2 * Fl.nint, ncd = 2 * Cl.nint;
+bool stabilised_transfer(const Level& Cl, const Level& Fl, const Averaging& Av, const std::vector<double>& B,
+                         bool transpose, bool general, CSR& Pc) {
+  const int nfd = 2 * Fl.nint;
   std::vector<std::map<int, double>> rows(nfd);
   for (int r = 0; r < nfd; ++r)
     for (int q = Av.row_ptr[r]; q < Av.row_ptr[r + 1]; ++q) rows[r][Av.col[q]] += Av.val[q];
@@ -224,7 +288,7 @@ bool stabilised_transfer(const Level& Cl, const Level& Fl, const Averaging& Av,
           int p2 = pos_of(f2);
           for (int a = 0; a < 2; ++a)
             for (int bb = 0; bb < 2; ++bb) {
-              double v = BK[(2 * i1 + a) * 6 + 2 * i2 + bb];
+              double v = transpose ? BK[(2 * i2 + bb) * 6 + 2 * i1 + a] : BK[(2 * i1 + a) * 6 + 2 * i2 + bb];
               if (p2 >= 0) ATT[(2 * p1 + a) * 6 + 2 * p2 + bb] += v;
               for (auto& kv : rows[2 * f2 + bb]) AI[2 * p1 + a][kv.first] += v * kv.second;
             }
@@ -232,7 +296,7 @@ bool stabilised_transfer(const Level& Cl, const Level& Fl, const Averaging& Av,
       }
     }
     std::vector<double> inv;
-    if (!invert_spd(ATT, 6, inv)) return false;
+    if (!(general ? invert_general(ATT, 6, inv) : invert_spd(ATT, 6, inv))) return false;
     for (int a = 0; a < 6; ++a) {
       int fr = 2 * inner[a / 2] + a % 2;
       for (int bb = 0; bb < 6; ++bb) {
@@ -243,29 +307,33 @@ bool stabilised_transfer(const Level& Cl, const Level& Fl, const Averaging& Av,
     }
   }
   Pc = CSR();
-  Rc = CSR();
   Pc.n = nfd;
-  Rc.n = ncd;
   Pc.rp.assign(1, 0);
-  std::vector<std::vector<std::pair<int, double>>> cols(ncd);
   for (int r = 0; r < nfd; ++r) {
     for (auto& kv : P[r]) {
       if (kv.second == 0.0) continue;
       Pc.ci.push_back(kv.first);
       Pc.v.push_back(kv.second);
-      cols[kv.first].push_back({r, kv.second});
     }
     Pc.rp.push_back((int)Pc.ci.size());
   }
-  Rc.rp.assign(1, 0);
-  for (int c = 0; c < ncd; ++c) {
-    for (auto& e : cols[c]) {
-      Rc.ci.push_back(e.first);
-      Rc.v.push_back(e.second);
-    }
-    Rc.rp.push_back((int)Rc.ci.size());
-  }
   return true;
+}
+
+void csr_transpose(const CSR& A, int ncols, CSR& T) {
+  std::vector<std::vector<std::pair<int, double>>> cols(ncols);
+  for (int r = 0; r < A.n; ++r)
+    for (int q = A.rp[r]; q < A.rp[r + 1]; ++q) cols[A.ci[q]].push_back({r, A.v[q]});
+  T = CSR();
+  T.n = ncols;
+  T.rp.assign(1, 0);
+  for (int c = 0; c < ncols; ++c) {
+    for (auto& e : cols[c]) {
+      T.ci.push_back(e.first);
+      T.v.push_back(e.second);
+    }
+    T.rp.push_back((int)T.ci.size());
+  }
 }
 
 void assemble_csr(const Level& L, const std::vector<double>& B, CSR& A) {
@@ -295,10 +363,7 @@ void assemble_csr(const Level& L, const std::vector<double>& B, CSR& A) {
   }
 }
 
-bool coarse_inverse(const Level& L0, const std::vector<double>& nu0, double beta, double eps_inv,
-                    std::vector<double>& inv) {
-  std::vector<double> B;
-  host_cr_blocks(L0, nu0, beta, eps_inv, B);
+bool coarse_inverse(const Level& L0, const std::vector<double>& B, bool general, std::vector<double>& inv) {
   const int n = 2 * L0.nint;
   std::vector<double> A((size_t)n * n, 0.0);
   for (int c = 0; c < L0.nc; ++c)
@@ -317,7 +382,7 @@ bool coarse_inverse(const Level& L0, const std::vector<double>& nu0, double beta
     inv.clear();
     return true;
   }
-  return invert_spd(A, n, inv);
+  return general ? invert_general(A, n, inv) : invert_spd(A, n, inv);
 }
 
 }  // namespace hdgmg

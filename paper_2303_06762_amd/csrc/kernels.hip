@@ -1,6 +1,8 @@
 // Device kernels of the skeleton solve (FP64).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace hdgmg {
@@ -11,63 +13,161 @@ constexpr int TPB = 256;
 
 inline int nblk(long n, int tpb = TPB) { return (int)((n + tpb - 1) / tpb); }
 
-__global__ void k_condense(QuadTables Q, const double* __restrict__ X, const int* __restrict__ cells,
-                           int c0, int nbatch, const double* __restrict__ nu, int nu_per_cell,
-                           double beta, double eps_inv, double* ws, double* S, int* status) {
+__global__ void k_condense(ElemLevel E, int c0, int nbatch, double* ws, double* S, int* status) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nbatch) return;
   int c = c0 + t;
   CellGeom g;
-  cell_geom(X, cells + 3 * c, g);
-  const int nK = 6 * (Q.k + 1);
-  double nuc = nu_per_cell ? nu[c] : nu[0];
-  int rc = element_local(Q, g, nuc, beta, eps_inv, EL_CONDENSE, nullptr, nullptr, 0.0,
-                         WS{ws + t, nbatch}, S + (long)c * nK * nK);
+  cell_geom(E.X, E.cells + 3 * c, g);
+  const int nK = 6 * (E.Q.k + 1);
+  double nuc = E.nu_per_cell ? E.nu[c] : E.nu[0];
+  int rc = element_local(E.Q, g, nuc, E.beta, E.eps_inv, EL_CONDENSE, nullptr, nullptr, 0.0, WS{ws + t, nbatch},
+                         S + (long)c * nK * nK, nullptr, nullptr, E.CT, E.wcoef ? E.wcoef + (long)c * E.na : nullptr);
   if (rc) atomicOr(status, 1);
 }
 
-__global__ void k_load(QuadTables Q, const double* __restrict__ X, const int* __restrict__ cells,
-                       int c0, int nbatch, const double* __restrict__ nu, int nu_per_cell,
-                       double beta, const double* __restrict__ f, double* ws, double* gK,
+// local tangential boundary values of cell c in the block's local order
+__device__ inline void boundary_local(const ElemLevel& E, int c, double* lb) {
+  const int m = E.m;
+  for (int i = 0; i < 6 * m; ++i) lb[i] = 0.0;
+  if (!E.bdl) return;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < m; ++j) lb[(i * 2 + 1) * m + j] = E.bdl[((long)c * 3 + i) * m + j];
+}
+
+__global__ void k_load(ElemLevel E, int c0, int nbatch, const double* __restrict__ f, double* ws, double* gK,
                        int* status) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nbatch) return;
   int c = c0 + t;
   CellGeom g;
-  cell_geom(X, cells + 3 * c, g);
-  const int nK = 6 * (Q.k + 1);
-  double nuc = nu_per_cell ? nu[c] : nu[0];
-  int rc = element_local(Q, g, nuc, beta, 0.0, EL_LOAD, f + (long)c * Q.nq * 2, nullptr, 0.0,
-                         WS{ws + t, nbatch}, gK + (long)c * nK);
+  cell_geom(E.X, E.cells + 3 * c, g);
+  const int nK = 6 * (E.Q.k + 1);
+  double nuc = E.nu_per_cell ? E.nu[c] : E.nu[0];
+  double* out = gK + (long)c * nK;
+  int rc = element_local(E.Q, g, nuc, E.beta, 0.0, EL_LOAD, f + (long)c * E.Q.nq * 2, nullptr, 0.0,
+                         WS{ws + t, nbatch}, out, nullptr, nullptr, E.CT,
+                         E.wcoef ? E.wcoef + (long)c * E.na : nullptr);
   if (rc) atomicOr(status, 1);
+  if (E.bdl) {
+    double lb[6 * (KMAX + 1)];
+    boundary_local(E, c, lb);
+    const double* SK = E.S + (long)c * nK * nK;
+    for (int r = 0; r < nK; ++r) {
+      double s = 0.0;
+      for (int q = 0; q < nK; ++q) s += SK[(long)r * nK + q] * lb[q];
+      out[r] -= s;
+    }
+  }
 }
 
-__global__ void k_recover(QuadTables Q, const double* __restrict__ X, const int* __restrict__ cells,
-                          int c0, int nbatch, const double* __restrict__ nu, int nu_per_cell,
-                          double beta, const double* __restrict__ f, const double* __restrict__ lam,
-                          const double* __restrict__ p0, int m, const int* __restrict__ cell_dofs,
-                          double* ws, double* u, double* p, int* status) {
+__global__ void k_recover(ElemLevel E, int c0, int nbatch, const double* __restrict__ f,
+                          const double* __restrict__ lam, const double* __restrict__ p0, double* ws, double* u,
+                          double* p, int* status) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nbatch) return;
   int c = c0 + t;
+  const int m = E.m;
   CellGeom g;
-  cell_geom(X, cells + 3 * c, g);
+  cell_geom(E.X, E.cells + 3 * c, g);
   double lk[6 * (KMAX + 1)];
+  boundary_local(E, c, lk);
   for (int i = 0; i < 3; ++i) {
-    int d = cell_dofs[3 * c + i];
+    int d = E.cell_dofs[3 * c + i];
+    if (d < 0) continue;
     for (int cc = 0; cc < 2; ++cc)
-      for (int j = 0; j < m; ++j) lk[(i * 2 + cc) * m + j] = d >= 0 ? lam[((long)d * 2 + cc) * m + j] : 0.0;
+      for (int j = 0; j < m; ++j) lk[(i * 2 + cc) * m + j] = lam[((long)d * 2 + cc) * m + j];
   }
   double out[3 * NQ_MAX];
-  double nuc = nu_per_cell ? nu[c] : nu[0];
-  int rc = element_local(Q, g, nuc, beta, 0.0, EL_RECOVER, f + (long)c * Q.nq * 2, lk, p0[c],
-                         WS{ws + t, nbatch}, out);
+  double nuc = E.nu_per_cell ? E.nu[c] : E.nu[0];
+  int rc = element_local(E.Q, g, nuc, E.beta, 0.0, EL_RECOVER, f + (long)c * E.Q.nq * 2, lk, p0[c],
+                         WS{ws + t, nbatch}, out, nullptr, nullptr, E.CT,
+                         E.wcoef ? E.wcoef + (long)c * E.na : nullptr);
   if (rc) atomicOr(status, 1);
-  for (int q = 0; q < Q.nq; ++q) {
-    u[((long)c * Q.nq + q) * 2] = out[2 * q];
-    u[((long)c * Q.nq + q) * 2 + 1] = out[2 * q + 1];
-    p[(long)c * Q.nq + q] = out[2 * Q.nq + q];
+  for (int q = 0; q < E.Q.nq; ++q) {
+    u[((long)c * E.Q.nq + q) * 2] = out[2 * q];
+    u[((long)c * E.Q.nq + q) * 2 + 1] = out[2 * q + 1];
+    p[(long)c * E.Q.nq + q] = out[2 * E.Q.nq + q];
   }
+}
+
+__global__ void k_wind_fit(QuadTables Q, const double* __restrict__ X, const int* __restrict__ cells, int c0,
+                           int nbatch, const double* __restrict__ vals, double* ws, double* coef, int* status) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nbatch) return;
+  const int c = c0 + t;
+  CellGeom g;
+  cell_geom(X, cells + 3 * c, g);
+  const int na = dims_of(Q.k).na;
+  if (wind_fit(Q, g, vals + (long)c * Q.nq * 2, WS{ws + t, nbatch}, coef + (long)c * na)) atomicOr(status, 1);
+}
+
+__global__ void k_wind_rt0(QuadTables Q0, const double* __restrict__ X, const int* __restrict__ cells,
+                           const int* __restrict__ cell_dofs, int c0, int nbatch, const double* __restrict__ flux,
+                           double* ws, double* coef, int* status) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nbatch) return;
+  const int c = c0 + t;
+  CellGeom g;
+  cell_geom(X, cells + 3 * c, g);
+  // the RT0 field with outward flux phi_i through local facet i:
+  // sum_i phi_i (x - x_i) / (2|K|), x_i the vertex opposite facet i
+  double phi[3], xv[3][2];
+  for (int i = 0; i < 3; ++i) {
+    int d = cell_dofs[3 * c + i];
+    phi[i] = d >= 0 ? g.sigma[i] * flux[d] : 0.0;
+    xv[i][0] = X[2 * cells[3 * c + i]];
+    xv[i][1] = X[2 * cells[3 * c + i] + 1];
+  }
+  double vals[2 * NQ_MAX];
+  for (int q = 0; q < Q0.nq; ++q) {
+    double x1 = Q0.xi[q][0], x2 = Q0.xi[q][1];
+    double xp[2] = {g.Xs0[0] + g.J[0][0] * x1 + g.J[0][1] * x2, g.Xs0[1] + g.J[1][0] * x1 + g.J[1][1] * x2};
+    double wx = 0.0, wy = 0.0;
+    for (int i = 0; i < 3; ++i) {
+      wx += phi[i] * (xp[0] - xv[i][0]);
+      wy += phi[i] * (xp[1] - xv[i][1]);
+    }
+    vals[2 * q] = wx / (2.0 * g.area);
+    vals[2 * q + 1] = wy / (2.0 * g.area);
+  }
+  if (wind_fit(Q0, g, vals, WS{ws + t, nbatch}, coef + (long)c * 3)) atomicOr(status, 1);
+}
+
+__global__ void k_facet_flux(QuadTables Q, const double* __restrict__ X, const int* __restrict__ cells,
+                             const int* __restrict__ fcell, const int* __restrict__ floc, int nint,
+                             const double* __restrict__ coef, int na, double* __restrict__ flux) {
+  int fi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (fi >= nint) return;
+  const int c = fcell[2 * fi], i = floc[2 * fi];
+  CellGeom g;
+  cell_geom(X, cells + 3 * c, g);
+  const Dims D = dims_of(Q.k);
+  const double* wc = coef + (long)c * na;
+  double u[2 * 40], gr[4 * 40], mono[16];
+  double s_ = 0.0;
+  for (int l = 0; l < Q.nfq; ++l) {
+    double s = Q.s[l];
+    double xp[2] = {g.P0[i][0] + s * (g.P1[i][0] - g.P0[i][0]), g.P0[i][1] + s * (g.P1[i][1] - g.P0[i][1])};
+    double dx = xp[0] - g.Xs0[0], dy = xp[1] - g.Xs0[1];
+    double x1 = g.Ji[0][0] * dx + g.Ji[0][1] * dy;
+    double x2 = g.Ji[1][0] * dx + g.Ji[1][1] * dy;
+    rt_basis(D, g, x1, x2, xp, u, gr, mono);
+    double wn = 0.0;
+    for (int a = 0; a < na; ++a) wn += wc[a] * (u[2 * a] * g.n[i][0] + u[2 * a + 1] * g.n[i][1]);
+    s_ += Q.ws[l] * wn;
+  }
+  flux[fi] = s_ * g.len[i];
+}
+
+__global__ void k_bd_local(int nc, int m, const int* __restrict__ cbf, const double* __restrict__ uhat_b,
+                           double* __restrict__ bdl) {
+  long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)nc * 3 * m) return;
+  const long ci = t / m;
+  const int j = (int)(t % m);
+  const int b = cbf[ci];
+  bdl[t] = b >= 0 ? uhat_b[(long)b * m + j] : 0.0;
 }
 
 // gnu[c] += -(Lift z, Lift z_adj)_K for the forward state (f, lam) and the
@@ -133,7 +233,7 @@ __global__ void k_cr_blocks(const double* __restrict__ X, const int* __restrict_
 // Assemble the principal block A_ss of every patch from the cell blocks and
 // invert it (Cholesky); one thread per patch, strided workspace.
 __global__ void k_patch_inverse(LevelView L, const int* __restrict__ pc_ptr, const int* __restrict__ pc,
-                                int npatch, int max_ns, double* ws, double* pinv, int* status) {
+                                int npatch, int max_ns, int general, double* ws, double* pinv, int* status) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= npatch) return;
   const int m2 = 2 * L.m;
@@ -162,6 +262,63 @@ __global__ void k_patch_inverse(LevelView L, const int* __restrict__ pc_ptr, con
       }
     }
   }
+  double* out = pinv + L.pinv_off[p];
+  if (general) {
+    // LU with partial pivoting (nonsymmetric blocks); row swaps kept after A
+    WS piv{ws + (long)max_ns * max_ns * npatch + p, npatch};
+    for (int j = 0; j < ns; ++j) {
+      int pr = j;
+      double best = fabs(A[(long)j * ns + j]);
+      for (int i = j + 1; i < ns; ++i) {
+        double v = fabs(A[(long)i * ns + j]);
+        if (v > best) {
+          best = v;
+          pr = i;
+        }
+      }
+      if (!(best > 0)) {
+        atomicOr(status, 2);
+        return;
+      }
+      piv[j] = (double)pr;
+      if (pr != j)
+        for (int c = 0; c < ns; ++c) {
+          double t = A[(long)j * ns + c];
+          A[(long)j * ns + c] = A[(long)pr * ns + c];
+          A[(long)pr * ns + c] = t;
+        }
+      const double dj = A[(long)j * ns + j];
+      for (int i = j + 1; i < ns; ++i) {
+        double l = A[(long)i * ns + j] / dj;
+        A[(long)i * ns + j] = l;
+        if (l != 0.0)
+          for (int c = j + 1; c < ns; ++c) A[(long)i * ns + c] -= l * A[(long)j * ns + c];
+      }
+    }
+    for (int c = 0; c < ns; ++c) {
+      double* col = out + (long)c * ns;  // column c of the inverse
+      for (int i = 0; i < ns; ++i) col[i] = i == c ? 1.0 : 0.0;
+      for (int j = 0; j < ns; ++j) {
+        int pr = (int)piv[j];
+        if (pr != j) {
+          double t = col[j];
+          col[j] = col[pr];
+          col[pr] = t;
+        }
+      }
+      for (int i = 0; i < ns; ++i) {
+        double s = col[i];
+        for (int q = 0; q < i; ++q) s -= A[(long)i * ns + q] * col[q];
+        col[i] = s;
+      }
+      for (int i = ns - 1; i >= 0; --i) {
+        double s = col[i];
+        for (int q = i + 1; q < ns; ++q) s -= A[(long)i * ns + q] * col[q];
+        col[i] = s / A[(long)i * ns + i];
+      }
+    }
+    return;
+  }
   // Cholesky (lower, in place)
   for (int j = 0; j < ns; ++j) {
     double d = A[(long)j * ns + j];
@@ -178,7 +335,6 @@ __global__ void k_patch_inverse(LevelView L, const int* __restrict__ pc_ptr, con
       A[(long)i * ns + j] = s / d;
     }
   }
-  double* out = pinv + L.pinv_off[p];
   for (int c = 0; c < ns; ++c) {
     double* col = out + (long)c * ns;  // column c of the inverse
     for (int i = 0; i < ns; ++i) {
@@ -366,6 +522,35 @@ __global__ void k_dot2(long n, const double* __restrict__ z, const double* __res
   }
 }
 
+// part[i * gridDim.x + block] = partial sums of V_i . w, i < nv (V_i = V + i * ld)
+__global__ void k_mdot(long n, int nv, const double* __restrict__ V, long ld, const double* __restrict__ w,
+                       double* part) {
+  __shared__ double sh[TPB];
+  for (int i = 0; i < nv; ++i) {
+    const double* v = V + (long)i * ld;
+    double s = 0.0;
+    for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x)
+      s += v[t] * w[t];
+    double r = block_sum(s, sh);
+    if (threadIdx.x == 0) part[(long)i * gridDim.x + blockIdx.x] = r;
+  }
+}
+
+// w += sign * sum_i h[i] V_i
+__global__ void k_maxpy(long n, int nv, const double* __restrict__ V, long ld, const double* __restrict__ h,
+                        double sign, double* __restrict__ w) {
+  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int i = 0; i < nv; ++i) s += h[i] * V[(long)i * ld + t];
+    w[t] += sign * s;
+  }
+}
+
+__global__ void k_scale(long n, double a, const double* __restrict__ x, double* __restrict__ y) {
+  long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) y[t] = a * x[t];
+}
+
 __global__ void k_finalize(const double* __restrict__ part, int nblocks, int nvals, double* sc, int slot0) {
   __shared__ double sh[TPB];
   for (int v = 0; v < nvals; ++v) {
@@ -442,24 +627,40 @@ __global__ void k_uzawa_update(int nc, int m, const int* __restrict__ cell_dofs,
 
 }  // namespace
 
-void launch_condense(hipStream_t st, const QuadTables& Q, const double* X, const int* cells, int c0,
-                     int nbatch, const double* nu, int nu_per_cell, double beta, double eps_inv,
-                     double* ws, double* S, int* status) {
-  hipLaunchKernelGGL(k_condense, dim3(nblk(nbatch, 64)), dim3(64), 0, st, Q, X, cells, c0, nbatch, nu,
-                     nu_per_cell, beta, eps_inv, ws, S, status);
+void launch_condense(hipStream_t st, const ElemLevel& E, int c0, int nbatch, double* ws, double* S, int* status) {
+  hipLaunchKernelGGL(k_condense, dim3(nblk(nbatch, 64)), dim3(64), 0, st, E, c0, nbatch, ws, S, status);
 }
-void launch_load(hipStream_t st, const QuadTables& Q, const double* X, const int* cells, int c0,
-                 int nbatch, const double* nu, int nu_per_cell, double beta, const double* f,
-                 double* ws, double* gK, int* status) {
-  hipLaunchKernelGGL(k_load, dim3(nblk(nbatch, 64)), dim3(64), 0, st, Q, X, cells, c0, nbatch, nu,
-                     nu_per_cell, beta, f, ws, gK, status);
+void launch_load(hipStream_t st, const ElemLevel& E, int c0, int nbatch, const double* f, double* ws, double* gK,
+                 int* status) {
+  hipLaunchKernelGGL(k_load, dim3(nblk(nbatch, 64)), dim3(64), 0, st, E, c0, nbatch, f, ws, gK, status);
 }
-void launch_recover(hipStream_t st, const QuadTables& Q, const double* X, const int* cells, int c0,
-                    int nbatch, const double* nu, int nu_per_cell, double beta, const double* f,
-                    const double* lam, const double* p0, int m, const int* cell_dofs, double* ws,
-                    double* u, double* p, int* status) {
-  hipLaunchKernelGGL(k_recover, dim3(nblk(nbatch, 64)), dim3(64), 0, st, Q, X, cells, c0, nbatch, nu,
-                     nu_per_cell, beta, f, lam, p0, m, cell_dofs, ws, u, p, status);
+void launch_recover(hipStream_t st, const ElemLevel& E, int c0, int nbatch, const double* f, const double* lam,
+                    const double* p0, double* ws, double* u, double* p, int* status) {
+  hipLaunchKernelGGL(k_recover, dim3(nblk(nbatch, 64)), dim3(64), 0, st, E, c0, nbatch, f, lam, p0, ws, u, p,
+                     status);
+}
+void launch_wind_fit(hipStream_t st, const QuadTables& Q, const double* X, const int* cells, int c0, int nbatch,
+                     const double* vals, double* ws, double* coef, int* status) {
+  if (nbatch > 0)
+    hipLaunchKernelGGL(k_wind_fit, dim3(nblk(nbatch, 64)), dim3(64), 0, st, Q, X, cells, c0, nbatch, vals, ws, coef,
+                       status);
+}
+void launch_wind_rt0(hipStream_t st, const QuadTables& Q0, const double* X, const int* cells,
+                     const int* cell_dofs, int c0, int nbatch, const double* flux, double* ws, double* coef,
+                     int* status) {
+  if (nbatch > 0)
+    hipLaunchKernelGGL(k_wind_rt0, dim3(nblk(nbatch, 64)), dim3(64), 0, st, Q0, X, cells, cell_dofs, c0, nbatch,
+                       flux, ws, coef, status);
+}
+void launch_facet_flux(hipStream_t st, const QuadTables& Q, const double* X, const int* cells, const int* fcell,
+                       const int* floc, int nint, const double* coef, int na, double* flux) {
+  if (nint > 0)
+    hipLaunchKernelGGL(k_facet_flux, dim3(nblk(nint, 64)), dim3(64), 0, st, Q, X, cells, fcell, floc, nint, coef,
+                       na, flux);
+}
+void launch_bd_local(hipStream_t st, int nc, int m, const int* cbf, const double* uhat_b, double* bdl) {
+  const long n = (long)nc * 3 * m;
+  if (n > 0) hipLaunchKernelGGL(k_bd_local, dim3(nblk(n)), dim3(TPB), 0, st, nc, m, cbf, uhat_b, bdl);
 }
 void launch_gradnu(hipStream_t st, const QuadTables& Q, const double* X, const int* cells, int c0, int nbatch,
                    const double* nu, int nu_per_cell, double beta, const double* f, const double* lam,
@@ -479,10 +680,10 @@ void launch_cr_blocks(hipStream_t st, const double* X, const int* cells, int nc,
                      eps_inv, A);
 }
 void launch_patch_inverse(hipStream_t st, LevelView L, const int* pc_ptr, const int* pc, int npatch,
-                          int max_ns, double* ws, double* pinv, int* status) {
+                          int max_ns, int general, double* ws, double* pinv, int* status) {
   if (npatch <= 0) return;
-  hipLaunchKernelGGL(k_patch_inverse, dim3(nblk(npatch, 64)), dim3(64), 0, st, L, pc_ptr, pc, npatch,
-                     max_ns, ws, pinv, status);
+  hipLaunchKernelGGL(k_patch_inverse, dim3(nblk(npatch, 64)), dim3(64), 0, st, L, pc_ptr, pc, npatch, max_ns,
+                     general, ws, pinv, status);
 }
 template <typename TS>
 void launch_apply(hipStream_t st, LevelViewT<TS> L, const double* x, double* y, double alpha, const double* b) {
@@ -554,6 +755,16 @@ void launch_dot2(hipStream_t st, long n, const double* z, const double* r, const
 }
 void launch_finalize(hipStream_t st, const double* part, int nblocks, int nvals, double* sc, int slot0) {
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(TPB), 0, st, part, nblocks, nvals, sc, slot0);
+}
+void launch_mdot(hipStream_t st, long n, int nv, const double* V, long ld, const double* w, double* part, int nb) {
+  if (nv > 0) hipLaunchKernelGGL(k_mdot, dim3(nb), dim3(TPB), 0, st, n, nv, V, ld, w, part);
+}
+void launch_maxpy(hipStream_t st, long n, int nv, const double* V, long ld, const double* h, double sign, double* w) {
+  if (nv > 0 && n > 0)
+    hipLaunchKernelGGL(k_maxpy, dim3(std::min<long>(nblk(n), 4096)), dim3(TPB), 0, st, n, nv, V, ld, h, sign, w);
+}
+void launch_scale(hipStream_t st, long n, double a, const double* x, double* y) {
+  if (n > 0) hipLaunchKernelGGL(k_scale, dim3(nblk(n)), dim3(TPB), 0, st, n, a, x, y);
 }
 void launch_fcg_xr(hipStream_t st, long n, double* x, double* r, double* r_old, const double* p,
                    const double* q, const double* sc, double* part, int nblocks) {

@@ -27,16 +27,43 @@ using LevelView = LevelViewT<double>;
 // Scalars of the flexible-CG recurrence kept on the device.
 enum { SC_ZR = 0, SC_PQ, SC_RR, SC_ZRN, SC_ZRO, SC_BB, SC_DP, SC_PP, SC_N };
 
-void launch_condense(hipStream_t st, const QuadTables& Q, const double* X, const int* cells,
-                     int c0, int nbatch, const double* nu, int nu_per_cell, double beta,
-                     double eps_inv, double* ws, double* S, int* status);
-void launch_load(hipStream_t st, const QuadTables& Q, const double* X, const int* cells, int c0,
-                 int nbatch, const double* nu, int nu_per_cell, double beta, const double* f,
-                 double* ws, double* gK, int* status);
-void launch_recover(hipStream_t st, const QuadTables& Q, const double* X, const int* cells,
-                    int c0, int nbatch, const double* nu, int nu_per_cell, double beta,
-                    const double* f, const double* lam, const double* p0, int m,
-                    const int* cell_dofs, double* ws, double* u, double* p, int* status);
+// What the per-cell local solver of one level needs.
+struct ElemLevel {
+  QuadTables Q;             // data rule of the level's order
+  const ConvTables* CT;     // device convection rules, or null (no wind)
+  const double* X;          // [nv][2]
+  const int* cells;         // [nc][3]
+  const double* nu;         // [nc] or [1]
+  int nu_per_cell;
+  double beta, eps_inv;
+  const double* wcoef;      // [nc][na] wind coefficients in the RT_k basis, or null
+  int na;
+  const int* cell_dofs;     // [nc][3] interior facet ids, -1 on the boundary
+  int m;
+  const double* bdl;        // [nc][3][m] prescribed tangential boundary values, or null
+  const double* S;          // [nc][nK][nK] condensed blocks (the loads' boundary lift)
+};
+
+void launch_condense(hipStream_t st, const ElemLevel& E, int c0, int nbatch, double* ws, double* S, int* status);
+// gK = g_K(f) - S_K lambda_K^b (boundary lift when E.bdl is set)
+void launch_load(hipStream_t st, const ElemLevel& E, int c0, int nbatch, const double* f, double* ws, double* gK,
+                 int* status);
+void launch_recover(hipStream_t st, const ElemLevel& E, int c0, int nbatch, const double* f, const double* lam,
+                    const double* p0, double* ws, double* u, double* p, int* status);
+// Wind coefficients of a field given at the data points ([nc][nq][2]) for
+// cells c0 .. c0+nbatch (workspace: nbatch * na * (na+1) doubles).
+void launch_wind_fit(hipStream_t st, const QuadTables& Q, const double* X, const int* cells, int c0, int nbatch,
+                     const double* vals, double* ws, double* coef, int* status);
+// Lowest-order wind: the RT0 field with the given flux per interior facet
+// (boundary fluxes zero), as coefficients in the k = 0 basis ([nc][3]).
+void launch_wind_rt0(hipStream_t st, const QuadTables& Q0, const double* X, const int* cells,
+                     const int* cell_dofs, int c0, int nbatch, const double* flux, double* ws, double* coef,
+                     int* status);
+// flux[F] = int_F w . n_F for every interior facet (from its first cell).
+void launch_facet_flux(hipStream_t st, const QuadTables& Q, const double* X, const int* cells, const int* fcell,
+                       const int* floc, int nint, const double* coef, int na, double* flux);
+// bdl[c][i][j] = uhat_b[cbf[3c+i]][j] (0 where cbf < 0).
+void launch_bd_local(hipStream_t st, int nc, int m, const int* cbf, const double* uhat_b, double* bdl);
 // gnu[c] += -(Lift z, Lift z_adj)_K for cells c0 .. c0+nbatch (forward
 // source f and skeleton vector lam, adjoint source fa and skeleton vector lama).
 void launch_gradnu(hipStream_t st, const QuadTables& Q, const double* X, const int* cells, int c0, int nbatch,
@@ -48,8 +75,10 @@ void launch_data_weight(hipStream_t st, const QuadTables& Q, const double* X, co
                         const double* in, int inverse, double* out);
 void launch_cr_blocks(hipStream_t st, const double* X, const int* cells, int nc,
                       const double* nu_cells, double beta, double eps_inv, double* A);
+// Inverses of the patch blocks A_ss (column-major): Cholesky, or LU with
+// partial pivoting when general != 0 (workspace max_ns^2 + max_ns per patch).
 void launch_patch_inverse(hipStream_t st, LevelView L, const int* pc_ptr, const int* pc,
-                          int npatch, int max_ns, double* ws, double* pinv, int* status);
+                          int npatch, int max_ns, int general, double* ws, double* pinv, int* status);
 // y = alpha * A x + (b ? b : 0)
 template <typename TS>
 void launch_apply(hipStream_t st, LevelViewT<TS> L, const double* x, double* y, double alpha,
@@ -78,6 +107,13 @@ void launch_dot2(hipStream_t st, long n, const double* z, const double* r, const
                  double* part, int nblocks);
 void launch_finalize(hipStream_t st, const double* part, int nblocks, int nvals, double* sc,
                      int slot0);
+// part[i * nb + block] = block partials of V_i . w for i < nv (V_i = V + i*ld);
+// reduce with launch_finalize(part, nb, nv, out, 0).
+void launch_mdot(hipStream_t st, long n, int nv, const double* V, long ld, const double* w, double* part, int nb);
+// w += sign * sum_{i < nv} h[i] V_i (h on the device)
+void launch_maxpy(hipStream_t st, long n, int nv, const double* V, long ld, const double* h, double sign, double* w);
+// y = a x
+void launch_scale(hipStream_t st, long n, double a, const double* x, double* y);
 void launch_fcg_xr(hipStream_t st, long n, double* x, double* r, double* r_old, const double* p,
                    const double* q, const double* sc, double* part, int nblocks);
 void launch_fcg_p(hipStream_t st, long n, double* p, const double* z, const double* sc);

@@ -51,8 +51,13 @@ struct DevLevel {
   std::vector<int> colour_ptr;
   double* nu = nullptr;  // per cell
   double *u = nullptr, *g = nullptr, *r = nullptr;  // multigrid vectors
+  // lowest-order wind (Oseen): facet fluxes and RT0 coefficients per cell
+  double* flux = nullptr;   // [nint]
+  double* wcoef = nullptr;  // [nc][3]
   // streaming layout (fast.hip), used when every patch has <= FAST_NF facets
   bool fast = false;
+  bool full = false;      // cell blocks stored in full (nonsymmetric operators)
+  long sp_words = 0;      // words per cell of the streaming cell blocks
   double* Sp = nullptr;   // packed SoA cell blocks
   int* cdof = nullptr;    // [3][nc] 2*facet+side or -1
   double* yF = nullptr;   // [nint][2][2m] per-side facet rows
@@ -147,6 +152,23 @@ struct hdgmg_ctx {
   std::vector<Level> lv;
   std::vector<Averaging> avg;
   QuadTables Q;
+  QuadTables Q0;              // data rule of the lowest-order levels
+  ConvTables* CTk = nullptr;  // device convection rules of order k and 0
+  ConvTables* CT0 = nullptr;
+  bool has_wind = false;
+  double* wcoef = nullptr;    // [n_cells][na] wind coefficients (order-k level)
+  // lowest-order cell blocks of every level on the host (transfers, coarse levels)
+  std::vector<std::vector<double>> hostB;
+  // tangential Dirichlet data on the finest boundary facets
+  std::vector<int> bfacets;   // boundary facets in facet order
+  int* cbf = nullptr;         // [n_cells][3] boundary facet number or -1
+  double* bdl = nullptr;      // [n_cells][3][k+1] local boundary values
+  bool has_bd = false;
+  // FGMRES basis: V [(restart+1)][N_skel], Z [restart][N_skel], scalars
+  double *gm_V = nullptr, *gm_Z = nullptr, *gm_h = nullptr, *gm_y = nullptr, *gm_part = nullptr;
+  // allocations of one hdgmg_assemble (released by the next one)
+  std::vector<std::pair<void*, size_t>> asm_allocs;
+  bool in_assemble = false;
   DevLevel K;
   std::vector<DevLevel> cr;
   std::vector<DevTransfer> tr;
@@ -207,7 +229,10 @@ hdgmg_status dalloc(hdgmg_ctx* ctx, T** p, size_t n) {
     ctx->err = "device allocation of " + std::to_string(n * sizeof(T)) + " bytes failed";
     return HDGMG_ENOMEM;
   }
-  ctx->allocs.push_back(v);
+  if (ctx->in_assemble)
+    ctx->asm_allocs.push_back({v, n * sizeof(T)});
+  else
+    ctx->allocs.push_back(v);
   ctx->bytes += n * sizeof(T);
   *p = (T*)v;
   return HDGMG_OK;
@@ -318,6 +343,8 @@ hdgmg_status upload_level(hdgmg_ctx* ctx, const Level& L, int m, DevLevel& D) {
   // streaming kernels pay off on large levels; small ones keep the one-launch
   // Gauss-Seidel phase
   D.fast = L.max_patch_facets <= FAST_NF && (long)L.nint * 2 * m >= ctx->opts.stream_dofs;
+  D.full = ctx->opts.oseen != 0;
+  D.sp_words = fast_cell_words(D.nK, D.full);
   if (D.fast) {
     const int m2 = 2 * m, nK = D.nK;
     std::vector<int> cd(3 * (size_t)L.nc, -1);
@@ -332,14 +359,14 @@ hdgmg_status upload_level(hdgmg_ctx* ctx, const Level& L, int m, DevLevel& D) {
         ncd += 1;
       }
     TRY(upload(ctx, &D.cdof, cd));
-    TRY(dalloc(ctx, &D.Sp, (size_t)L.nc * fast_cell_words(nK)));
+    TRY(dalloc(ctx, &D.Sp, (size_t)L.nc * D.sp_words));
     TRY(dalloc(ctx, &D.yF, (size_t)L.nint * 2 * m2));
     // compulsory bytes of one cell apply: the blocks, the facet map, x once
     // per interior facet, y_F once per (cell, interior facet)
     const double vec = ((double)L.nint + ncd) * m2 * 8.0 + L.nc * 12.0;
-    D.bytes_cell = (double)L.nc * fast_cell_words(nK) * 8.0 + vec;
+    D.bytes_cell = (double)L.nc * D.sp_words * 8.0 + vec;
     const double ws = ctx->opts.vcycle_precision == 1 ? 4.0 : 8.0;
-    D.bytes_cell_vc = (double)L.nc * fast_cell_words(nK) * ws + vec;
+    D.bytes_cell_vc = (double)L.nc * D.sp_words * ws + vec;
     D.bytes_sum = 3.0 * L.nint * m2 * 8.0;
     const int NS = FAST_NF * m2;
     for (int cc = 0; cc < L.ncol; ++cc) {
@@ -380,13 +407,14 @@ hdgmg_status check_status(hdgmg_ctx* ctx, const char* what) {
 }
 
 hdgmg_status patch_inverses(hdgmg_ctx* ctx, DevLevel& D) {
-  size_t need = (size_t)D.max_ns * D.max_ns * D.npatch * sizeof(double);
+  size_t need = ((size_t)D.max_ns * D.max_ns + D.max_ns) * D.npatch * sizeof(double);
   if (need > ctx->ws_bytes) {
     ctx->err = "patch workspace too small";
     return HDGMG_ENOMEM;
   }
   HIPC(hipMemsetAsync(ctx->status, 0, sizeof(int), ctx->st));
-  launch_patch_inverse(ctx->st, D.view(), D.pc_ptr, D.pc, D.npatch, D.max_ns, ctx->ws, D.pinv, ctx->status);
+  launch_patch_inverse(ctx->st, D.view(), D.pc_ptr, D.pc, D.npatch, D.max_ns, ctx->opts.oseen ? 1 : 0, ctx->ws,
+                       D.pinv, ctx->status);
   HIPC(hipGetLastError());
   return check_status(ctx, "patch inverse");
 }
@@ -394,7 +422,7 @@ hdgmg_status patch_inverses(hdgmg_ctx* ctx, DevLevel& D) {
 // Pack the cell blocks and patch inverses of a level into the streaming layout.
 hdgmg_status pack_fast(hdgmg_ctx* ctx, DevLevel& D) {
   if (!D.fast) return HDGMG_OK;
-  launch_pack_cells(ctx->st, D.nc, D.nK, D.S, D.Sp);
+  launch_pack_cells(ctx->st, D.nc, D.nK, D.S, D.Sp, D.full);
   for (size_t c = 0; c < D.npc.size(); ++c)
     launch_pack_patches(ctx->st, D.npc[c], D.colour_ptr[c], 2 * D.m, D.pf_ptr, D.pinv_off, D.pinv, D.Ppc[c]);
   HIPC(hipGetLastError());
@@ -411,7 +439,7 @@ hdgmg_status make_f32(hdgmg_ctx* ctx, DevLevel& D) {
   TRY(dalloc(ctx, &D.pinv32, (size_t)std::max(D.pinv_len, 1L)));
   launch_to_f32(ctx->st, D.pinv_len, D.pinv, D.pinv32);
   if (D.fast) {
-    long nSp = (long)D.nc * fast_cell_words(D.nK);
+    long nSp = (long)D.nc * D.sp_words;
     TRY(dalloc(ctx, &D.Sp32, (size_t)nSp));
     launch_to_f32(ctx->st, nSp, D.Sp, D.Sp32);
     const long NS = (long)FAST_NF * 2 * D.m;
@@ -449,9 +477,9 @@ void sweep(hdgmg_ctx* ctx, DevLevel& D, double* x, const double* b, bool forward
       // colour phase = cell apply (all cells) + patch relaxation (colour c)
       int t = kt_begin(ctx, level < 0 ? 1 : 2);
       if (D.f32)
-        launch_cell_apply<float>(ctx->st, 2 * D.m, D.nc, D.Sp32, D.cdof, x, D.yF);
+        launch_cell_apply<float>(ctx->st, 2 * D.m, D.nc, D.Sp32, D.cdof, x, D.yF, D.full);
       else
-        launch_cell_apply<double>(ctx->st, 2 * D.m, D.nc, D.Sp, D.cdof, x, D.yF);
+        launch_cell_apply<double>(ctx->st, 2 * D.m, D.nc, D.Sp, D.cdof, x, D.yF, D.full);
       kt_end(ctx, level < 0 ? 1 : 2, t, D.bytes_cell_vc);
       t = kt_begin(ctx, level < 0 ? 0 : 2);
       if (D.f32)
@@ -479,9 +507,9 @@ void level_apply(hdgmg_ctx* ctx, DevLevel& D, const double* x, double* y, double
   if (D.fast) {
     int t = kt_begin(ctx, cls);
     if (f32)
-      launch_cell_apply<float>(ctx->st, 2 * D.m, D.nc, D.Sp32, D.cdof, x, D.yF);
+      launch_cell_apply<float>(ctx->st, 2 * D.m, D.nc, D.Sp32, D.cdof, x, D.yF, D.full);
     else
-      launch_cell_apply<double>(ctx->st, 2 * D.m, D.nc, D.Sp, D.cdof, x, D.yF);
+      launch_cell_apply<double>(ctx->st, 2 * D.m, D.nc, D.Sp, D.cdof, x, D.yF, D.full);
     kt_end(ctx, cls, t, f32 ? D.bytes_cell_vc : D.bytes_cell);
     launch_facet_sum(ctx->st, D.nint, 2 * D.m, D.yF, b, alpha, y);
   } else {
@@ -666,22 +694,145 @@ hdgmg_status fcg(hdgmg_ctx* ctx, const double* b, double* x, int* its_out, doubl
   return HDGMG_NOT_CONVERGED;
 }
 
+// Flexible GMRES(restart) with right preconditioning by MG_hp (Sec. 4.2),
+// from the iterate in x.  Orthogonalisation: classical Gram-Schmidt applied
+// twice (two fused passes over the basis; the same projections as modified
+// Gram-Schmidt in exact arithmetic).  The Hessenberg least-squares problem
+// (Givens rotations) is solved on the host, one transfer of the new column
+// per iteration.  Stops at |residual estimate| <= max(rtol ||r_0||, atol).
+hdgmg_status fgmres(hdgmg_ctx* ctx, const double* b, double* x, int* its_out, double* rel_out) {
+  const long n = ctx->K.ndof;
+  const int m = ctx->opts.restart, NB = RED_BLOCKS;
+  hipStream_t st = ctx->st;
+  double* V = ctx->gm_V;
+  double* Z = ctx->gm_Z;
+  auto Vj = [&](int j) { return V + (long)j * n; };
+  auto Zj = [&](int j) { return Z + (long)j * n; };
+  auto norm_of = [&](const double* v, double* out) -> hdgmg_status {
+    launch_dot(st, n, v, v, ctx->part, NB);
+    launch_finalize(st, ctx->part, NB, 1, ctx->sc, SC_BB);
+    double hs[SC_N];
+    HIPC(hipMemcpyAsync(hs, ctx->sc, sizeof(hs), hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    *out = std::sqrt(hs[SC_BB]);
+    return HDGMG_OK;
+  };
+  apply_k(ctx, x, Vj(0), -1.0, b);  // r = b - A x
+  double beta;
+  TRY(norm_of(Vj(0), &beta));
+  if (!std::isfinite(beta)) {
+    ctx->err = "non-finite residual";
+    return HDGMG_ENONFINITE;
+  }
+  const double beta0 = beta, tol = std::max(ctx->opts.rtol * beta0, ctx->opts.atol);
+  if (its_out) *its_out = 0;
+  if (rel_out) *rel_out = beta0 > 0 ? 1.0 : 0.0;
+  if (beta <= tol) return HDGMG_OK;
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), hb(4 * 128);
+  int its = 0;
+  double res = beta;
+  while (true) {
+    launch_scale(st, n, 1.0 / beta, Vj(0), Vj(0));
+    std::fill(H.begin(), H.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int jend = 0;
+    for (int j = 0; j < m; ++j) {
+      // z_j = MG_hp(v_j) through the preconditioner's fixed buffers
+      launch_copy(st, n, Vj(j), ctx->r);
+      mg_hp(ctx, ctx->r, ctx->z);
+      launch_copy(st, n, ctx->z, Zj(j));
+      double* w = Vj(j + 1);
+      apply_k(ctx, Zj(j), w, 1.0, nullptr);
+      for (int pass = 0; pass < 2; ++pass) {
+        launch_mdot(st, n, j + 1, V, n, w, ctx->gm_part, NB);
+        launch_finalize(st, ctx->gm_part, NB, j + 1, ctx->gm_h + 128 * pass, 0);
+        launch_maxpy(st, n, j + 1, V, n, ctx->gm_h + 128 * pass, -1.0, w);
+      }
+      launch_dot(st, n, w, w, ctx->part, NB);
+      launch_finalize(st, ctx->part, NB, 1, ctx->gm_h + 256, 0);
+      HIPC(hipGetLastError());
+      HIPC(hipMemcpyAsync(hb.data(), ctx->gm_h, hb.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPC(hipStreamSynchronize(st));
+      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hb[i] + hb[128 + i];
+      const double hn = std::sqrt(std::max(hb[256], 0.0));
+      if (!std::isfinite(hn)) {
+        ctx->err = "non-finite value in FGMRES";
+        return HDGMG_ENONFINITE;
+      }
+      if (hn > 0.0) launch_scale(st, n, 1.0 / hn, w, w);
+      H[(size_t)(j + 1) * m + j] = hn;
+      for (int i = 0; i < j; ++i) {
+        const double a = H[(size_t)i * m + j], c = H[(size_t)(i + 1) * m + j];
+        H[(size_t)i * m + j] = cs[i] * a + sn[i] * c;
+        H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
+      }
+      const double a = H[(size_t)j * m + j], den = std::hypot(a, hn);
+      if (!(den > 0.0)) {
+        ctx->err = "FGMRES breakdown (zero Hessenberg column)";
+        return HDGMG_EBREAKDOWN;
+      }
+      cs[j] = a / den;
+      sn[j] = hn / den;
+      H[(size_t)j * m + j] = den;
+      H[(size_t)(j + 1) * m + j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++its;
+      jend = j + 1;
+      res = std::fabs(g[j + 1]);
+      if (res <= tol || its >= ctx->opts.max_it || hn == 0.0) break;
+    }
+    for (int i = jend - 1; i >= 0; --i) {
+      double t = g[i];
+      for (int q = i + 1; q < jend; ++q) t -= H[(size_t)i * m + q] * y[q];
+      y[i] = t / H[(size_t)i * m + i];
+    }
+    HIPC(hipMemcpyAsync(ctx->gm_y, y.data(), jend * sizeof(double), hipMemcpyHostToDevice, st));
+    launch_maxpy(st, n, jend, Z, n, ctx->gm_y, 1.0, x);
+    HIPC(hipStreamSynchronize(st));  // y is read before it goes out of scope
+    if (its_out) *its_out = its;
+    if (rel_out) *rel_out = res / beta0;
+    if (res <= tol) return HDGMG_OK;
+    if (its >= ctx->opts.max_it) break;
+    apply_k(ctx, x, Vj(0), -1.0, b);
+    TRY(norm_of(Vj(0), &beta));
+    if (!std::isfinite(beta)) {
+      ctx->err = "non-finite residual";
+      return HDGMG_ENONFINITE;
+    }
+    if (beta <= tol) {
+      if (rel_out) *rel_out = beta / beta0;
+      return HDGMG_OK;
+    }
+  }
+  ctx->err = "inner solve reached max_it";
+  return HDGMG_NOT_CONVERGED;
+}
+
 hdgmg_status build_transfers(hdgmg_ctx* ctx) {
-  const double eps_inv = ctx->gamma;
   ctx->tr.assign(ctx->J, DevTransfer());
-  std::vector<std::vector<double>> nu;
-  level_viscosities(ctx->lv, ctx->nu_fine, nu);
-  for (int l = 0; l < ctx->J; ++l) TRY(upload(ctx, &ctx->cr[l].nu, nu[l]));
+  const bool general = ctx->opts.oseen != 0;
   for (int l = 1; l < ctx->J; ++l) {
     CSR P, R;
-    if (!stabilised_transfer(ctx->lv[l - 1], ctx->lv[l], ctx->avg[l], nu[l], ctx->beta, eps_inv, P, R)) {
+    // prolongation harmonic for A; restriction the transpose of the same
+    // construction for A^T (the transpose of P when A is symmetric)
+    bool ok = stabilised_transfer(ctx->lv[l - 1], ctx->lv[l], ctx->avg[l], ctx->hostB[l], false, general, P);
+    if (ok && ctx->has_wind) {
+      CSR Pt;
+      ok = stabilised_transfer(ctx->lv[l - 1], ctx->lv[l], ctx->avg[l], ctx->hostB[l], true, general, Pt);
+      csr_transpose(Pt, 2 * ctx->lv[l - 1].nint, R);
+    } else {
+      csr_transpose(P, 2 * ctx->lv[l - 1].nint, R);
+    }
+    if (!ok) {
       ctx->err = "singular interior block in harmonic extension";
       return HDGMG_ENONFINITE;
     }
     DevTransfer& Tt = ctx->tr[l];
     Tt.nfine = P.n;
     Tt.ncoarse = R.n;
-    Tt.nnz = (long)P.ci.size();
+    Tt.nnz = (long)std::max(P.ci.size(), R.ci.size());
     TRY(upload(ctx, &Tt.P_rp, P.rp));
     TRY(upload(ctx, &Tt.P_ci, P.ci));
     TRY(upload(ctx, &Tt.P_v, P.v));
@@ -704,8 +855,8 @@ hdgmg_status build_transfers(hdgmg_ctx* ctx) {
     if (ctx->opts.vcycle_precision == 1) TRY(upload_f32(ctx, &Tt.Re_v32, ev));
   }
   std::vector<double> inv;
-  if (!coarse_inverse(ctx->lv[0], nu[0], ctx->beta, eps_inv, inv)) {
-    ctx->err = "coarsest operator not positive definite";
+  if (!coarse_inverse(ctx->lv[0], ctx->hostB[0], general, inv)) {
+    ctx->err = general ? "coarsest operator singular" : "coarsest operator not positive definite";
     return HDGMG_ENONFINITE;
   }
   ctx->n0 = 2 * ctx->lv[0].nint;
@@ -730,8 +881,6 @@ hdgmg_status build_coarse(hdgmg_ctx* ctx) {
     Lc = l;
   }
   if (Lc < 0) return HDGMG_OK;
-  std::vector<std::vector<double>> nu;
-  level_viscosities(ctx->lv, ctx->nu_fine, nu);
   std::vector<CoarseLevel> desc(Lc + 1);
   int off = COARSE_THREADS + 32;
   for (int l = 0; l <= Lc; ++l) {
@@ -748,10 +897,8 @@ hdgmg_status build_coarse(hdgmg_ctx* ctx) {
     C.u_glob = D.u;
     C.g_glob = D.g;
     if (l == 0) continue;
-    std::vector<double> B;
-    host_cr_blocks(L, nu[l], ctx->beta, ctx->gamma, B);
     CSR A;
-    assemble_csr(L, B, A);
+    assemble_csr(L, ctx->hostB[l], A);
     // per-unknown padded rows
     std::vector<int> rw_col((size_t)COARSE_NNZ * n, 0);
     std::vector<double> rw_val((size_t)COARSE_NNZ * n, 0.0);
@@ -782,7 +929,7 @@ hdgmg_status build_coarse(hdgmg_ctx* ctx) {
           for (int q = A.rp[dofs[i]]; q < A.rp[dofs[i] + 1]; ++q)
             for (int j = 0; j < ns; ++j)
               if (A.ci[q] == dofs[j]) Ass[(size_t)i * ns + j] = A.v[q];
-        if (!invert_spd(Ass, ns, inv)) {
+        if (!(ctx->opts.oseen ? invert_general(Ass, ns, inv) : invert_spd(Ass, ns, inv))) {
           ctx->err = "singular patch block on a coarse level";
           return HDGMG_ENONFINITE;
         }
@@ -791,7 +938,7 @@ hdgmg_status build_coarse(hdgmg_ctx* ctx) {
           idof.push_back(dofs[i]);
           iloc.push_back(i);
           std::vector<double> row(nsm, 0.0);
-          for (int j = 0; j < ns; ++j) row[j] = inv[(size_t)i * ns + j];  // symmetric
+          for (int j = 0; j < ns; ++j) row[j] = inv[(size_t)j * ns + i];  // row i (inv column-major)
           irow.push_back(row);
         }
       }
@@ -875,33 +1022,94 @@ hdgmg_status build_coarse(hdgmg_ctx* ctx) {
   return HDGMG_OK;
 }
 
-hdgmg_status batched(hdgmg_ctx* ctx, int nc, int k, int mode, const double* f, const double* lam,
-                     const double* p0, double* out1, double* out2, const double* f2 = nullptr,
+// Element data of a level for the local solver kernels.  wind: with the
+// level's wind coefficients (order-k: ctx->wcoef; lowest order: D.wcoef).
+ElemLevel elem_level(const hdgmg_ctx* ctx, const DevLevel& D, bool order_k, bool wind) {
+  ElemLevel E;
+  E.Q = order_k ? ctx->Q : ctx->Q0;
+  E.CT = nullptr;
+  E.wcoef = nullptr;
+  E.na = dims_of(E.Q.k).na;
+  if (wind && ctx->has_wind) {
+    E.CT = order_k ? ctx->CTk : ctx->CT0;
+    E.wcoef = order_k ? ctx->wcoef : D.wcoef;
+  }
+  E.X = D.X;
+  E.cells = D.cells;
+  E.nu = D.nu;
+  E.nu_per_cell = 1;
+  E.beta = ctx->beta;
+  E.eps_inv = ctx->gamma;
+  E.cell_dofs = D.cell_dofs;
+  E.m = D.m;
+  E.bdl = order_k && ctx->has_bd ? ctx->bdl : nullptr;
+  E.S = D.S;
+  return E;
+}
+
+// Local solver kernels over all cells of a level in workspace-sized batches.
+hdgmg_status batched(hdgmg_ctx* ctx, DevLevel& D, const ElemLevel& E, int mode, const double* f,
+                     const double* lam, const double* p0, double* out1, double* out2, const double* f2 = nullptr,
                      const double* lam2 = nullptr) {
-  long per = element_ws_size(k);
+  const int nc = D.nc;
+  long per = element_ws_size(E.Q.k);
   long batch = std::max<long>(1, std::min<long>(nc, (long)(ctx->ws_bytes / (per * sizeof(double)))));
   HIPC(hipMemsetAsync(ctx->status, 0, sizeof(int), ctx->st));
-  DevLevel& D = ctx->K;
   for (long c0 = 0; c0 < nc; c0 += batch) {
     int nb = (int)std::min<long>(batch, nc - c0);
     if (mode == EL_CONDENSE)
-      launch_condense(ctx->st, ctx->Q, D.X, D.cells, (int)c0, nb, D.nu, 1, ctx->beta, ctx->gamma, ctx->ws,
-                      D.S, ctx->status);
+      launch_condense(ctx->st, E, (int)c0, nb, ctx->ws, out1, ctx->status);
     else if (mode == EL_LOAD)
-      launch_load(ctx->st, ctx->Q, D.X, D.cells, (int)c0, nb, D.nu, 1, ctx->beta, f, ctx->ws, out1,
-                  ctx->status);
+      launch_load(ctx->st, E, (int)c0, nb, f, ctx->ws, out1, ctx->status);
     else if (mode == EL_GRADNU)
-      launch_gradnu(ctx->st, ctx->Q, D.X, D.cells, (int)c0, nb, D.nu, 1, ctx->beta, f, lam, f2, lam2, D.m,
+      launch_gradnu(ctx->st, E.Q, D.X, D.cells, (int)c0, nb, D.nu, 1, ctx->beta, f, lam, f2, lam2, D.m,
                     D.cell_dofs, ctx->ws, out1, ctx->status);
     else
-      launch_recover(ctx->st, ctx->Q, D.X, D.cells, (int)c0, nb, D.nu, 1, ctx->beta, f, lam, p0, D.m,
-                     D.cell_dofs, ctx->ws, out1, out2, ctx->status);
+      launch_recover(ctx->st, E, (int)c0, nb, f, lam, p0, ctx->ws, out1, out2, ctx->status);
     HIPC(hipGetLastError());
   }
   return check_status(ctx, mode == EL_CONDENSE ? "condensation"
                            : mode == EL_LOAD   ? "load"
                            : mode == EL_GRADNU ? "viscosity gradient"
                                                : "recovery");
+}
+
+// Order-k blocks and patch factors, lowest-order blocks (closed form, or
+// the generic k = 0 condensation with the level's RT0 wind), transfers and
+// coarse-level data.
+hdgmg_status assemble_levels(hdgmg_ctx* ctx) {
+  TRY(batched(ctx, ctx->K, elem_level(ctx, ctx->K, true, true), EL_CONDENSE, nullptr, nullptr, nullptr, ctx->K.S,
+              nullptr));
+  TRY(patch_inverses(ctx, ctx->K));
+  TRY(pack_fast(ctx, ctx->K));
+  TRY(make_f32(ctx, ctx->K));
+  ctx->hostB.assign(ctx->J, {});
+  std::vector<std::vector<double>> nu;
+  level_viscosities(ctx->lv, ctx->nu_fine, nu);
+  for (int l = 0; l < ctx->J; ++l) {
+    DevLevel& D = ctx->cr[l];
+    if (ctx->has_wind) {
+      TRY(batched(ctx, D, elem_level(ctx, D, false, true), EL_CONDENSE, nullptr, nullptr, nullptr, D.S, nullptr));
+      ctx->hostB[l].resize((size_t)D.nc * 36);
+      HIPC(hipMemcpyAsync(ctx->hostB[l].data(), D.S, ctx->hostB[l].size() * sizeof(double),
+                          hipMemcpyDeviceToHost, ctx->st));
+      HIPC(hipStreamSynchronize(ctx->st));
+    } else {
+      launch_cr_blocks(ctx->st, D.X, D.cells, D.nc, D.nu, ctx->beta, ctx->gamma, D.S);
+      HIPC(hipGetLastError());
+      host_cr_blocks(ctx->lv[l], nu[l], ctx->beta, ctx->gamma, ctx->hostB[l]);
+    }
+  }
+  TRY(build_transfers(ctx));
+  for (int l = 1; l < ctx->J; ++l) {
+    DevLevel& D = ctx->cr[l];
+    TRY(patch_inverses(ctx, D));
+    TRY(pack_fast(ctx, D));
+    TRY(make_f32(ctx, D));
+  }
+  TRY(build_coarse(ctx));
+  HIPC(hipStreamSynchronize(ctx->st));
+  return HDGMG_OK;
 }
 
 }  // namespace
@@ -922,6 +1130,8 @@ void hdgmg_default_opts(hdgmg_opts* o) {
   o->coarse_dofs = 2048;
   o->stream_dofs = 200000;
   o->vcycle_precision = 0;
+  o->oseen = 0;
+  o->restart = 50;
 }
 
 const char* hdgmg_last_error(const hdgmg_ctx* ctx) {
@@ -974,7 +1184,8 @@ hdgmg_status hdgmg_setup(const hdgmg_mesh* mesh, int k, double beta, const doubl
   if (ctx->opts.m_relax < 0 || ctx->opts.m_smooth < 1 || ctx->opts.cycle < 1 || ctx->opts.cycle > 2 ||
       ctx->opts.vcycle_growth < 1 || ctx->opts.max_it < 1 || ctx->opts.uzawa_max < 1 ||
       ctx->opts.uzawa_max > HDGMG_MAX_UZAWA || !(ctx->opts.rtol >= 0) || !(ctx->opts.atol >= 0) ||
-      ctx->opts.vcycle_precision < 0 || ctx->opts.vcycle_precision > 1) {
+      ctx->opts.vcycle_precision < 0 || ctx->opts.vcycle_precision > 1 || ctx->opts.oseen < 0 ||
+      ctx->opts.oseen > 1 || ctx->opts.restart < 1 || ctx->opts.restart > 64) {
     g_setup_error = "invalid options";
     delete ctx;
     return HDGMG_EINVAL;
@@ -1030,6 +1241,44 @@ hdgmg_status hdgmg_setup(const hdgmg_mesh* mesh, int k, double beta, const doubl
   ctx->cr.resize(ctx->J);
   for (int l = 0; l < ctx->J; ++l)
     if ((s = upload_level(ctx, ctx->lv[l], 1, ctx->cr[l]))) return fail(s);
+  {
+    std::vector<std::vector<double>> nul;
+    level_viscosities(ctx->lv, ctx->nu_fine, nul);
+    for (int l = 0; l < ctx->J; ++l)
+      if ((s = upload(ctx, &ctx->cr[l].nu, nul[l]))) return fail(s);
+  }
+  ctx->Q0 = make_tables(0);
+  if (ctx->opts.oseen) {
+    // convection rules, wind storage, FGMRES basis
+    std::vector<ConvTables> ct = {make_conv_tables(k)}, ct0 = {make_conv_tables(0)};
+    if ((s = upload(ctx, &ctx->CTk, ct))) return fail(s);
+    if ((s = upload(ctx, &ctx->CT0, ct0))) return fail(s);
+    if ((s = dalloc(ctx, &ctx->wcoef, (size_t)LF.nc * dims_of(k).na))) return fail(s);
+    for (auto& D : ctx->cr) {
+      if ((s = dalloc(ctx, &D.flux, (size_t)std::max(D.nint, 1)))) return fail(s);
+      if ((s = dalloc(ctx, &D.wcoef, (size_t)D.nc * 3))) return fail(s);
+    }
+    const size_t nv = (size_t)std::max<long>(ctx->K.ndof, 1);
+    if ((s = dalloc(ctx, &ctx->gm_V, nv * (ctx->opts.restart + 1)))) return fail(s);
+    if ((s = dalloc(ctx, &ctx->gm_Z, nv * ctx->opts.restart))) return fail(s);
+    if ((s = dalloc(ctx, &ctx->gm_h, 4 * 128))) return fail(s);
+    if ((s = dalloc(ctx, &ctx->gm_y, 128))) return fail(s);
+    if ((s = dalloc(ctx, &ctx->gm_part, (size_t)(ctx->opts.restart + 1) * RED_BLOCKS))) return fail(s);
+  }
+  {
+    // boundary facets of the finest level in facet order, and per cell side
+    std::vector<int> num(LF.nf, -1);
+    for (int f = 0; f < LF.nf; ++f)
+      if (LF.int_id[f] < 0) {
+        num[f] = (int)ctx->bfacets.size();
+        ctx->bfacets.push_back(f);
+      }
+    std::vector<int> cbf(3 * (size_t)LF.nc);
+    for (int c = 0; c < LF.nc; ++c)
+      for (int i = 0; i < 3; ++i) cbf[3 * c + i] = num[LF.cell_facets[3 * c + i]];
+    if ((s = upload(ctx, &ctx->cbf, cbf))) return fail(s);
+    if ((s = dalloc(ctx, &ctx->bdl, (size_t)LF.nc * 3 * (k + 1)))) return fail(s);
+  }
   const long n = ctx->K.ndof;
   double** vecs[] = {&ctx->x, &ctx->r, &ctx->r_old, &ctx->z, &ctx->p, &ctx->q, &ctx->b, &ctx->gvec, &ctx->lam};
   for (double** v : vecs)
@@ -1059,8 +1308,10 @@ hdgmg_status hdgmg_setup(const hdgmg_mesh* mesh, int k, double beta, const doubl
   if ((s = upload(ctx, &ctx->area, area))) return fail(s);
   // workspace: element batches and patch factorisations share it
   size_t need = 0;
-  for (auto* D : {&ctx->K}) need = std::max(need, (size_t)D->max_ns * D->max_ns * D->npatch * sizeof(double));
-  for (auto& D : ctx->cr) need = std::max(need, (size_t)D.max_ns * D.max_ns * D.npatch * sizeof(double));
+  for (auto* D : {&ctx->K})
+    need = std::max(need, ((size_t)D->max_ns * D->max_ns + D->max_ns) * D->npatch * sizeof(double));
+  for (auto& D : ctx->cr)
+    need = std::max(need, ((size_t)D.max_ns * D.max_ns + D.max_ns) * D.npatch * sizeof(double));
   size_t el = (size_t)element_ws_size(k) * sizeof(double) * std::min<long>(LF.nc, 16384);
   need = std::max(need, el);
   ctx->ws_bytes = need;
@@ -1093,21 +1344,16 @@ hdgmg_status hdgmg_assemble(hdgmg_ctx* ctx) {
   if (!ctx) return HDGMG_EINVAL;
   ctx->assembled = false;
   drop_graph(ctx);
-  TRY(batched(ctx, ctx->K.nc, ctx->k, EL_CONDENSE, nullptr, nullptr, nullptr, nullptr, nullptr));
-  TRY(patch_inverses(ctx, ctx->K));
-  TRY(pack_fast(ctx, ctx->K));
-  TRY(make_f32(ctx, ctx->K));
-  TRY(build_transfers(ctx));
-  for (int l = 0; l < ctx->J; ++l) {
-    DevLevel& D = ctx->cr[l];
-    launch_cr_blocks(ctx->st, D.X, D.cells, D.nc, D.nu, ctx->beta, ctx->gamma, D.S);
-    HIPC(hipGetLastError());
-    if (l > 0) TRY(patch_inverses(ctx, D));
-    if (l > 0) TRY(pack_fast(ctx, D));
-    if (l > 0) TRY(make_f32(ctx, D));
-  }
-  TRY(build_coarse(ctx));
   HIPC(hipStreamSynchronize(ctx->st));
+  for (auto& a : ctx->asm_allocs) {
+    (void)hipFree(a.first);
+    ctx->bytes -= a.second;
+  }
+  ctx->asm_allocs.clear();
+  ctx->in_assemble = true;
+  hdgmg_status s = assemble_levels(ctx);
+  ctx->in_assemble = false;
+  if (s != HDGMG_OK) return s;
   // algorithmic bytes of one MG_hp application (sum over its launches,
   // operators in the storage precision the V-cycle reads)
   {
@@ -1144,7 +1390,7 @@ hdgmg_status hdgmg_rhs(hdgmg_ctx* ctx, const double* f_qp, double* g) {
     ctx->err = "hdgmg_rhs before hdgmg_assemble";
     return HDGMG_ESTATE;
   }
-  TRY(batched(ctx, ctx->K.nc, ctx->k, EL_LOAD, f_qp, nullptr, nullptr, ctx->gK, nullptr));
+  TRY(batched(ctx, ctx->K, elem_level(ctx, ctx->K, true, true), EL_LOAD, f_qp, nullptr, nullptr, ctx->gK, nullptr));
   launch_gather_cells(ctx->st, ctx->K.view(), ctx->gK, g);
   HIPC(hipGetLastError());
   HIPC(hipStreamSynchronize(ctx->st));
@@ -1181,9 +1427,90 @@ hdgmg_status hdgmg_inner_solve(hdgmg_ctx* ctx, const double* b, double* x, int* 
     ctx->err = "hdgmg_inner_solve before hdgmg_assemble";
     return HDGMG_ESTATE;
   }
-  hdgmg_status s = fcg(ctx, b, x, its, rel_res);
+  hdgmg_status s;
+  if (ctx->opts.oseen) {
+    launch_fill(ctx->st, ctx->K.ndof, 0.0, x);
+    s = fgmres(ctx, b, x, its, rel_res);
+  } else {
+    s = fcg(ctx, b, x, its, rel_res);
+  }
   HIPC(hipStreamSynchronize(ctx->st));
   return s;
+}
+
+hdgmg_status hdgmg_set_wind(hdgmg_ctx* ctx, const double* w_qp) {
+  if (!ctx) return HDGMG_EINVAL;
+  if (!ctx->opts.oseen) {
+    ctx->err = "hdgmg_set_wind needs a context set up with opts.oseen = 1";
+    return HDGMG_ESTATE;
+  }
+  drop_graph(ctx);
+  ctx->assembled = false;
+  ctx->has_wind = false;
+  if (!w_qp) return HDGMG_OK;
+  hipStream_t st = ctx->st;
+  DevLevel& KL = ctx->K;
+  const int na = dims_of(ctx->k).na;
+  // RT_k coefficients of the wind on the order-k level
+  long per = (long)na * (na + 1);
+  long batch = std::max<long>(1, std::min<long>(KL.nc, (long)(ctx->ws_bytes / (per * sizeof(double)))));
+  HIPC(hipMemsetAsync(ctx->status, 0, sizeof(int), st));
+  for (long c0 = 0; c0 < KL.nc; c0 += batch)
+    launch_wind_fit(st, ctx->Q, KL.X, KL.cells, (int)c0, (int)std::min<long>(batch, KL.nc - c0), w_qp, ctx->ws,
+                    ctx->wcoef, ctx->status);
+  HIPC(hipGetLastError());
+  TRY(check_status(ctx, "wind fit"));
+  // facet fluxes on the finest level, summed over facet halves downwards
+  const int J = ctx->J;
+  std::vector<std::vector<double>> fl(J);
+  fl[J - 1].resize(KL.nint);
+  launch_facet_flux(st, ctx->Q, KL.X, KL.cells, KL.fcell, KL.floc, KL.nint, ctx->wcoef, na, ctx->cr[J - 1].flux);
+  HIPC(hipGetLastError());
+  if (KL.nint > 0)
+    HIPC(hipMemcpyAsync(fl[J - 1].data(), ctx->cr[J - 1].flux, KL.nint * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPC(hipStreamSynchronize(st));
+  for (int l = J - 1; l > 0; --l) {
+    const Level& F = ctx->lv[l];
+    const Level& C = ctx->lv[l - 1];
+    fl[l - 1].assign(C.nint, 0.0);
+    for (int f = 0; f < F.nf; ++f) {
+      const int a = F.edges[2 * f], b = F.edges[2 * f + 1];
+      if (a >= C.nv || b < C.nv || F.int_id[f] < 0) continue;
+      const int E = b - C.nv;  // the coarse facet this half lies on
+      if (C.int_id[E] < 0) continue;
+      const double sgn = F.norm[2 * f] * C.norm[2 * E] + F.norm[2 * f + 1] * C.norm[2 * E + 1];
+      fl[l - 1][C.int_id[E]] += fl[l][F.int_id[f]] * sgn;
+    }
+    if (C.nint > 0)
+      HIPC(hipMemcpyAsync(ctx->cr[l - 1].flux, fl[l - 1].data(), C.nint * sizeof(double), hipMemcpyHostToDevice,
+                          st));
+    HIPC(hipStreamSynchronize(st));
+  }
+  // RT0 winds of the lowest-order levels
+  HIPC(hipMemsetAsync(ctx->status, 0, sizeof(int), st));
+  for (int l = 0; l < J; ++l) {
+    DevLevel& D = ctx->cr[l];
+    long b0 = std::max<long>(1, std::min<long>(D.nc, (long)(ctx->ws_bytes / (12 * sizeof(double)))));
+    for (long c0 = 0; c0 < D.nc; c0 += b0)
+      launch_wind_rt0(st, ctx->Q0, D.X, D.cells, D.cell_dofs, (int)c0, (int)std::min<long>(b0, D.nc - c0), D.flux,
+                      ctx->ws, D.wcoef, ctx->status);
+  }
+  HIPC(hipGetLastError());
+  TRY(check_status(ctx, "lowest-order wind"));
+  HIPC(hipStreamSynchronize(st));
+  ctx->has_wind = true;
+  return HDGMG_OK;
+}
+
+hdgmg_status hdgmg_set_dirichlet(hdgmg_ctx* ctx, const double* uhat_b) {
+  if (!ctx) return HDGMG_EINVAL;
+  ctx->has_bd = false;
+  if (!uhat_b) return HDGMG_OK;
+  launch_bd_local(ctx->st, ctx->K.nc, ctx->k + 1, ctx->cbf, uhat_b, ctx->bdl);
+  HIPC(hipGetLastError());
+  HIPC(hipStreamSynchronize(ctx->st));
+  ctx->has_bd = true;
+  return HDGMG_OK;
 }
 
 hdgmg_status hdgmg_recover(hdgmg_ctx* ctx, const double* f_qp, const double* state, double* u_qp,
@@ -1193,13 +1520,19 @@ hdgmg_status hdgmg_recover(hdgmg_ctx* ctx, const double* f_qp, const double* sta
     ctx->err = "hdgmg_recover before hdgmg_assemble";
     return HDGMG_ESTATE;
   }
-  TRY(batched(ctx, ctx->K.nc, ctx->k, EL_RECOVER, f_qp, state, state + ctx->K.ndof, u_qp, p_qp));
+  TRY(batched(ctx, ctx->K, elem_level(ctx, ctx->K, true, true), EL_RECOVER, f_qp, state, state + ctx->K.ndof, u_qp,
+              p_qp));
   HIPC(hipStreamSynchronize(ctx->st));
   return HDGMG_OK;
 }
 
 hdgmg_status hdgmg_solve(hdgmg_ctx* ctx, const double* f_qp, double* u_qp, double* p_qp, double* state,
                          hdgmg_info* info) {
+  return hdgmg_solve_x0(ctx, f_qp, nullptr, u_qp, p_qp, state, info);
+}
+
+hdgmg_status hdgmg_solve_x0(hdgmg_ctx* ctx, const double* f_qp, const double* x0, double* u_qp, double* p_qp,
+                            double* state, hdgmg_info* info) {
   if (!ctx || !f_qp || !u_qp || !p_qp) return HDGMG_EINVAL;
   if (!ctx->assembled) {
     ctx->err = "hdgmg_solve before hdgmg_assemble";
@@ -1208,6 +1541,10 @@ hdgmg_status hdgmg_solve(hdgmg_ctx* ctx, const double* f_qp, double* u_qp, doubl
   if (info) std::memset(info, 0, sizeof(*info));
   hipStream_t st = ctx->st;
   const DevLevel& KL = ctx->K;
+  if (x0)
+    launch_copy(st, KL.ndof, x0, ctx->lam);
+  else
+    launch_fill(st, KL.ndof, 0.0, ctx->lam);
   TRY(hdgmg_rhs(ctx, f_qp, ctx->gvec));
   launch_fill(st, KL.nc, 0.0, ctx->p0);
   hdgmg_status result = HDGMG_OK;
@@ -1215,7 +1552,9 @@ hdgmg_status hdgmg_solve(hdgmg_ctx* ctx, const double* f_qp, double* u_qp, doubl
     launch_uzawa_rhs(st, KL.nint, KL.m, ctx->gvec, ctx->fdiv, KL.fcell, ctx->p0, ctx->b);
     int its = 0;
     double rel = 0.0;
-    hdgmg_status s = fcg(ctx, ctx->b, ctx->lam, &its, &rel);
+    // Oseen: FGMRES from the latest iterate; Stokes: flexible CG from zero
+    hdgmg_status s = ctx->opts.oseen ? fgmres(ctx, ctx->b, ctx->lam, &its, &rel)
+                                     : fcg(ctx, ctx->b, ctx->lam, &its, &rel);
     if (s < 0) return s;
     if (s == HDGMG_NOT_CONVERGED) result = s;
     launch_uzawa_update(st, KL.nc, KL.m, KL.cell_dofs, ctx->cdiv, ctx->area, ctx->lam, ctx->gamma, ctx->p0,
@@ -1259,6 +1598,10 @@ hdgmg_status hdgmg_solve_adjoint(hdgmg_ctx* ctx, const double* f_qp, const doubl
     ctx->err = "hdgmg_solve_adjoint before hdgmg_assemble";
     return HDGMG_ESTATE;
   }
+  if (ctx->has_wind || ctx->has_bd) {
+    ctx->err = "hdgmg_solve_adjoint with a wind or Dirichlet data is not provided";
+    return HDGMG_ESTATE;
+  }
   const DevLevel& KL = ctx->K;
   const long nqd = (long)KL.nc * ctx->Q.nq;
   if (!ctx->adj_f) {
@@ -1275,7 +1618,9 @@ hdgmg_status hdgmg_solve_adjoint(hdgmg_ctx* ctx, const double* f_qp, const doubl
   // dJ/df = w_q |K| u_adj(x_q)
   launch_data_weight(ctx->st, ctx->Q, KL.X, KL.cells, KL.nc, gf_qp, 0, gf_qp);
   HIPC(hipGetLastError());
-  if (gnu) TRY(batched(ctx, KL.nc, ctx->k, EL_GRADNU, f_qp, state, nullptr, gnu, nullptr, ctx->adj_f, ast));
+  if (gnu)
+    TRY(batched(ctx, ctx->K, elem_level(ctx, ctx->K, true, false), EL_GRADNU, f_qp, state, nullptr, gnu, nullptr,
+                ctx->adj_f, ast));
   HIPC(hipStreamSynchronize(ctx->st));
   return result;
 }
@@ -1322,6 +1667,7 @@ hdgmg_status hdgmg_query(const hdgmg_ctx* ctx, int what, int level, int64_t* val
       if (level < 0 || level >= ctx->J) return HDGMG_EINVAL;
       *value = what == 8 ? ctx->lv[level].nc : 2L * ctx->lv[level].nint;
       return HDGMG_OK;
+    case 10: *value = (int64_t)ctx->bfacets.size(); return HDGMG_OK;
     default: return HDGMG_EINVAL;
   }
 }
@@ -1329,12 +1675,29 @@ hdgmg_status hdgmg_query(const hdgmg_ctx* ctx, int what, int level, int64_t* val
 hdgmg_status hdgmg_export(const hdgmg_ctx* cctx, int what, int level, void* dst, size_t bytes) {
   hdgmg_ctx* ctx = const_cast<hdgmg_ctx*>(cctx);
   if (!ctx || !dst) return HDGMG_EINVAL;
-  if (!ctx->assembled) {
-    ctx->err = "hdgmg_export before hdgmg_assemble";
+  if (!ctx->assembled && (what == 0 || what == 1)) {
+    ctx->err = "hdgmg_export of an operator before hdgmg_assemble";
     return HDGMG_ESTATE;
   }
   const double* src = nullptr;
   size_t n = 0;
+  if (what == 3) {
+    const Level& LF = ctx->lv.back();
+    n = ctx->bfacets.size() * 4;
+    if (bytes < n * sizeof(double)) {
+      ctx->err = "hdgmg_export: destination too small";
+      return HDGMG_EINVAL;
+    }
+    std::vector<double> e(std::max<size_t>(n, 1));
+    for (size_t i = 0; i < ctx->bfacets.size(); ++i) {
+      const int f = ctx->bfacets[i];
+      for (int v = 0; v < 2; ++v)
+        for (int d = 0; d < 2; ++d) e[4 * i + 2 * v + d] = LF.X[2 * (size_t)LF.edges[2 * f + v] + d];
+    }
+    if (n > 0) HIPC(hipMemcpyAsync(dst, e.data(), n * sizeof(double), hipMemcpyHostToDevice, ctx->st));
+    HIPC(hipStreamSynchronize(ctx->st));
+    return HDGMG_OK;
+  }
   if (what == 0) {
     src = ctx->K.S;
     n = (size_t)ctx->K.nc * ctx->K.nK * ctx->K.nK;

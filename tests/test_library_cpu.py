@@ -13,7 +13,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def declared_symbols():
     src = open(os.path.join(ROOT, "include", "hdgmg.h")).read()
-    pat = r"^(?:hdgmg_status|void|const char\*)\s+(hdgmg_[a-z_]+)\s*\("
+    pat = r"^(?:hdgmg_status|void|const char\*)\s+(hdgmg_[a-z0-9_]+)\s*\("
     return sorted(set(re.findall(pat, src, flags=re.M)))
 
 
@@ -30,7 +30,8 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts_match_header():
     # hdgmg_mesh: int, int, ptr, int, ptr, int; hdgmg_opts; hdgmg_info
     assert ctypes.sizeof(hd.Mesh) == 40
-    assert ctypes.sizeof(hd.Opts) == 4 * 4 + 8 * 2 + 4 * 2 + 8 + 4 * 3 + 4
+    # 4 ints, 2 doubles, 2 ints, a double, 5 ints, padded to 8
+    assert ctypes.sizeof(hd.Opts) == 4 * 4 + 8 * 2 + 4 * 2 + 8 + 4 * 5 + 4
     assert ctypes.sizeof(hd.Info) == 4 + 64 * 4 + 4 + 64 * 8 * 2
 
 
@@ -40,3 +41,4 @@ def test_default_opts_from_library():
     o = hd.default_opts()
     assert (o.m_relax, o.m_smooth, o.cycle, o.vcycle_growth) == (1, 1, 1, 2)
     assert o.rtol == 1e-8 and o.atol == 1e-10 and o.max_it == 500
+    assert o.oseen == 0 and o.restart == 50
