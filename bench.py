@@ -69,6 +69,91 @@ def cpu_baseline(k, beta, gamma, reps):
             "seconds": round(dt, 3)}
 
 
+def oseen_workload(hd, synth, torch, np, steps, re, k=3, n_refine=5):
+    """Lid-driven cavity: 128x128 squares (32768 cells, 6 levels), k = 3,
+    beta = 0, nu = 1/Re, eps^-1 = 1e2 nu, lid uhat = (1,0) on the top side,
+    body force sum_{a,b=1..3} c_ab sin(a pi x) sin(b pi y) (c ~ U[-1,1),
+    seed 2); a Stokes solve then `steps` Picard steps, each AL-Uzawa with
+    FGMRES(50) preconditioned by the FP32-storage V-cycle.  Timed: the
+    solves (each step's re-assembly reported separately)."""
+    c, t = synth.kuhn_square(4)
+    nu = 1.0 / re
+    s = hd.Solver(c, t, n_refine, k, 0.0, nu, 1e2 * nu, oseen=1, vcycle_precision=1)
+    X = s.data_points().cpu().numpy()
+    coef = synth.uniform_pm1(2, 0, (2, 3, 3))
+    f = np.zeros(X.shape)
+    for i in range(2):
+        for a in range(3):
+            for b in range(3):
+                f[..., i] += coef[i, a, b] * np.sin((a + 1) * np.pi * X[..., 0]) * np.sin((b + 1) * np.pi * X[..., 1])
+    f = torch.as_tensor(f, device="cuda")
+    s.set_dirichlet(s.lid_data())
+    t_solve = t_asm = 0.0
+    its, dus, x0, u_prev = [], [], None, None
+    for n in range(steps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.set_wind(None if u_prev is None else u_prev)
+        s.assemble()
+        torch.cuda.synchronize()
+        t_asm += time.perf_counter() - t0
+        t0 = time.perf_counter()
+        u, p, state, info, st = s.solve(f, x0=x0)
+        torch.cuda.synchronize()
+        t_solve += time.perf_counter() - t0
+        its.append(info["its"])
+        if u_prev is not None:
+            dus.append(float((u - u_prev).abs().max()))
+        u_prev, x0 = u, state[:s.n_skel]
+    out = {"workload": f"lid-driven cavity, 128x128 structured triangulation ({s.n_cells} cells, {s.levels} "
+                       f"levels), k={k}, Re={re:g}, beta=0, eps^-1=1e2 nu; Stokes solve + {steps} Picard steps",
+           "n_skel": s.n_skel, "value": s.n_skel * (steps + 1) / t_solve, "unit": "skeleton DOFs/s",
+           "solve_s": t_solve, "assemble_s_total": t_asm, "fgmres_its_per_uzawa_step": its,
+           "picard_max_du": dus,
+           "precision": "V-cycle operators FP32, FGMRES(50) and everything else FP64"}
+    s.close()
+    return out
+
+
+def adjoint_workload(hd, synth, torch, np, nrhs):
+    """Batch gradient: 128x128 squares (32768 cells), k = 2, beta = 1,
+    eps^-1 = 1e2, per-cell nu = exp(0.5 Z) (Z ~ N(0,1), seed 3); sources
+    f_i ~ U[-1,1) (seeds 100..), target u_t ~ U[-1,1) (seed 4); loss
+    sum_i sum_{K,q} w_q |K| |u_i - u_t|^2; forward solves and adjoint
+    solves (gradients w.r.t. f_i and nu) with the FP32-storage V-cycle.
+    Timed: forward + backward of the autograd function."""
+    c, t = synth.kuhn_square(4)
+    nr, k = 5, 2
+    n_cells = 32 * 4 ** nr
+    nu = np.exp(0.5 * synth.normal(3, 0, n_cells))
+    s = hd.Solver(c, t, nr, k, 1.0, nu, 1e2, vcycle_precision=1)
+    s.assemble()
+    nq = s.n_q
+    F = torch.as_tensor(np.stack([synth.source_uniform(100 + i, 1, n_cells, nq)[0] for i in range(nrhs)]),
+                        device="cuda").requires_grad_(True)
+    ut = torch.as_tensor(synth.source_uniform(4, 1, n_cells, nq)[0], device="cuda")
+    nu_t = torch.as_tensor(nu, device="cuda").requires_grad_(True)
+    W = s.data_weights()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u = hd.stokes_solve(s, F, nu_t)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    J = (W[None, :, :, None] * (u - ut[None]) ** 2).sum()
+    t0 = time.perf_counter()
+    J.backward()
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t0
+    out = {"workload": f"batch gradient, 128x128 structured triangulation ({n_cells} cells), k={k}, beta=1, "
+                       f"eps^-1=1e2, log-normal per-cell nu, {nrhs} sources; forward + adjoint solves",
+           "n_skel": s.n_skel, "value": 2 * nrhs * s.n_skel / (t_fwd + t_bwd), "unit": "skeleton DOFs/s",
+           "forward_s": t_fwd, "backward_s": t_bwd,
+           "grad_norms": {"f": float(F.grad.norm()), "nu": float(nu_t.grad.norm())},
+           "precision": "V-cycle operators FP32, flexible CG and everything else FP64"}
+    s.close()
+    return out
+
+
 def copy_bandwidth(torch, reps=5):
     """Read + write bandwidth of a plain 1 GiB device copy (HIP events)."""
     src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
@@ -97,6 +182,11 @@ def main():
     ap.add_argument("--gamma", type=float, default=1e2)
     ap.add_argument("--cpu-reps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-oseen", action="store_true", help="skip the lid-driven cavity Picard workload")
+    ap.add_argument("--picard-steps", type=int, default=10)
+    ap.add_argument("--re", type=float, default=100.0)
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the batch-gradient workload")
+    ap.add_argument("--adjoint-rhs", type=int, default=16)
     ap.add_argument("--profile-run", action="store_true",
                     help="counter-collection run: a 1 GiB device copy (calibration of the HBM "
                          "counters) then two FP64 inner solves; prints a summary only")
@@ -222,6 +312,10 @@ def main():
         "kernel_classes": classes(tm),
         "setup_s": m64["t_setup"], "assemble_s": m64["t_assemble"],
     }
+    if not a.no_oseen:
+        out["oseen"] = oseen_workload(hd, synth, torch, np, a.picard_steps, a.re)
+    if not a.no_adjoint:
+        out["adjoint"] = adjoint_workload(hd, synth, torch, np, a.adjoint_rhs)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(a.k, a.beta, a.gamma, a.cpu_reps)
     print(json.dumps(out), flush=True)

@@ -255,6 +255,7 @@ hdgmg_status hdgmg_query(const hdgmg_ctx* ctx, int what, int level, int64_t* val
  *   what 3: end points of the finest boundary facets, in facet order,
  *           [n_boundary_facets][2][2] (vertex v0 < v1 first: t_F points
  *           from the first to the second)
+ *   what 4: data-rule weights times cell areas, w_q |K|, [n_cells][n_q]
  * Local DOF order inside a block: (local facet i, component c, mode j) ->
  * (i*2 + c)*m + j, local facet i opposite the cell's i-th stored vertex.
  * `bytes` is the size of dst; EINVAL if too small. */

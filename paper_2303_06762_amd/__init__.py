@@ -248,6 +248,12 @@ class Solver:
         homogeneous)."""
         self._check(lib().hdgmg_set_dirichlet(self._h, ctypes.c_void_p(None) if uhat_b is None else _ptr(uhat_b)))
 
+    def data_weights(self):
+        """w_q |K| at the data points [n_cells][n_q] (integrals of data-point fields)."""
+        out = self.torch.empty((self.n_cells, self.n_q), dtype=self.torch.float64, device="cuda")
+        self._check(lib().hdgmg_export(self._h, 4, 0, _ptr(out), out.numel() * 8))
+        return out
+
     def boundary_facets(self):
         """End points [n_boundary_facets][2][2] of the boundary facets (facet order)."""
         nb = self.query(10)

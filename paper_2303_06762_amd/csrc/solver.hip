@@ -1681,6 +1681,20 @@ hdgmg_status hdgmg_export(const hdgmg_ctx* cctx, int what, int level, void* dst,
   }
   const double* src = nullptr;
   size_t n = 0;
+  if (what == 4) {
+    const Level& LF = ctx->lv.back();
+    n = (size_t)LF.nc * ctx->Q.nq;
+    if (bytes < n * sizeof(double)) {
+      ctx->err = "hdgmg_export: destination too small";
+      return HDGMG_EINVAL;
+    }
+    std::vector<double> w(n);
+    for (int c = 0; c < LF.nc; ++c)
+      for (int q = 0; q < ctx->Q.nq; ++q) w[(size_t)c * ctx->Q.nq + q] = ctx->Q.wq[q] * LF.area[c];
+    HIPC(hipMemcpyAsync(dst, w.data(), n * sizeof(double), hipMemcpyHostToDevice, ctx->st));
+    HIPC(hipStreamSynchronize(ctx->st));
+    return HDGMG_OK;
+  }
   if (what == 3) {
     const Level& LF = ctx->lv.back();
     n = ctx->bfacets.size() * 4;

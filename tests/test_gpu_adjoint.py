@@ -109,6 +109,8 @@ def test_autograd_batch_matches_oracle():
     _note("autograd batch: 3 sources, 128 cells, k=2")
     s = hd.Solver(c, t, nr, k, beta, nu, gamma)
     s.assemble()
+    Wg = host(s.data_weights())
+    assert np.abs(Wg - W).max() <= 1e-14 * np.abs(W).max()
     f_t = dev(F).requires_grad_(True)
     nu_t = dev(nu).requires_grad_(True)
     u = hd.stokes_solve(s, f_t, nu_t)
