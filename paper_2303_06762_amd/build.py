@@ -25,7 +25,7 @@ def build(verbose=False):
         subprocess.run(cmd, check=True)
         objs.append(obj)
     tmp = OUT + ".tmp"
-    cmd = [hipcc, "-shared", "--offload-arch=gfx950", "-fPIC", "-o", tmp] + objs
+    cmd = [hipcc, "-shared", "--offload-arch=gfx950", "-fPIC", "-pthread", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -1,9 +1,12 @@
 // Host-side numeric setup (quadrature tables, transfers, coarsest inverse).
 #include "host_setup.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <atomic>
 #include <map>
+#include <thread>
 
 namespace hdgmg {
 
@@ -259,13 +262,39 @@ void level_viscosities(const std::vector<Level>& lv, const std::vector<double>& 
 bool stabilised_transfer(const Level& Cl, const Level& Fl, const Averaging& Av, const std::vector<double>& B,
                          bool transpose, bool general, CSR& Pc) {
   const int nfd = 2 * Fl.nint;
-  std::vector<std::map<int, double>> rows(nfd);
+  // rows of P in fixed-capacity slots (the averaging rows have <= 10 entries,
+  // the corrected interior rows the coarse unknowns of a coarse cell and its
+  // three neighbours)
+  constexpr int CAP = 24;
+  std::vector<int> pc((size_t)nfd * CAP), pn(nfd, 0);
+  std::vector<double> pv((size_t)nfd * CAP);
+  std::atomic<bool> overflow(false);
+  auto add_to = [&](int r, int c, double v) {
+    int* ci = &pc[(size_t)r * CAP];
+    double* cv = &pv[(size_t)r * CAP];
+    for (int e = 0; e < pn[r]; ++e)
+      if (ci[e] == c) {
+        cv[e] += v;
+        return;
+      }
+    if (pn[r] == CAP) {
+      overflow = true;
+      return;
+    }
+    ci[pn[r]] = c;
+    cv[pn[r]++] = v;
+  };
+  // P starts as the averaging I (duplicate columns merged)
   for (int r = 0; r < nfd; ++r)
-    for (int q = Av.row_ptr[r]; q < Av.row_ptr[r + 1]; ++q) rows[r][Av.col[q]] += Av.val[q];
-  std::vector<std::map<int, double>> P(rows);
+    for (int q = Av.row_ptr[r]; q < Av.row_ptr[r + 1]; ++q) add_to(r, Av.col[q], Av.val[q]);
   // harmonic correction inside every coarse cell: rows of the interior fine
-  // DOFs become I - A_TT^-1 (A I)_T
-  for (int T = 0; T < Cl.nc; ++T) {
+  // DOFs become I - A_TT^-1 (A I)_T (A I from the unmodified averaging rows).
+  // Coarse cells own disjoint interior rows: ranges of them run in parallel.
+  std::atomic<bool> failed(false);
+  auto cells = [&](int T0, int T1) {
+  std::vector<int> cols;
+  std::vector<double> AI, ATT(36), inv;
+  for (int T = T0; T < T1 && !failed; ++T) {
     int inner[3];
     for (int i = 0; i < 3; ++i) inner[i] = Av.inner_facets[3 * T + i];
     auto pos_of = [&](int fi) {
@@ -273,44 +302,85 @@ bool stabilised_transfer(const Level& Cl, const Level& Fl, const Averaging& Av, 
         if (inner[i] == fi) return i;
       return -1;
     };
-    std::vector<double> ATT(36, 0.0);
-    std::vector<std::map<int, double>> AI(6);
+    std::fill(ATT.begin(), ATT.end(), 0.0);
+    cols.clear();
+    AI.clear();  // [column slot][6]
+    auto slot = [&](int c) {
+      for (size_t i = 0; i < cols.size(); ++i)
+        if (cols[i] == c) return (int)i;
+      cols.push_back(c);
+      AI.resize(AI.size() + 6, 0.0);
+      return (int)cols.size() - 1;
+    };
+    int sl[32];
     for (int ch = 0; ch < 4; ++ch) {
       int Kc = 4 * T + ch;
       const double* BK = &B[(size_t)Kc * 36];
+      int p1s[3];
       for (int i1 = 0; i1 < 3; ++i1) {
         int f1 = Fl.cell_dofs[3 * Kc + i1];
-        int p1 = f1 >= 0 ? pos_of(f1) : -1;
-        if (p1 < 0) continue;
-        for (int i2 = 0; i2 < 3; ++i2) {
-          int f2 = Fl.cell_dofs[3 * Kc + i2];
-          if (f2 < 0) continue;
-          int p2 = pos_of(f2);
-          for (int a = 0; a < 2; ++a)
-            for (int bb = 0; bb < 2; ++bb) {
+        p1s[i1] = f1 >= 0 ? pos_of(f1) : -1;
+      }
+      for (int i2 = 0; i2 < 3; ++i2) {
+        int f2 = Fl.cell_dofs[3 * Kc + i2];
+        if (f2 < 0) continue;
+        int p2 = pos_of(f2);
+        for (int bb = 0; bb < 2; ++bb) {
+          const int r = 2 * f2 + bb;
+          const int q0 = Av.row_ptr[r], nq = std::min(Av.row_ptr[r + 1] - q0, 32);
+          if (Av.row_ptr[r + 1] - q0 > 32) {
+            failed = true;
+            return;
+          }
+          for (int q = 0; q < nq; ++q) sl[q] = slot(Av.col[q0 + q]);
+          for (int i1 = 0; i1 < 3; ++i1) {
+            const int p1 = p1s[i1];
+            if (p1 < 0) continue;
+            for (int a = 0; a < 2; ++a) {
               double v = transpose ? BK[(2 * i2 + bb) * 6 + 2 * i1 + a] : BK[(2 * i1 + a) * 6 + 2 * i2 + bb];
               if (p2 >= 0) ATT[(2 * p1 + a) * 6 + 2 * p2 + bb] += v;
-              for (auto& kv : rows[2 * f2 + bb]) AI[2 * p1 + a][kv.first] += v * kv.second;
+              for (int q = 0; q < nq; ++q) AI[(size_t)sl[q] * 6 + 2 * p1 + a] += v * Av.val[q0 + q];
             }
+          }
         }
       }
     }
-    std::vector<double> inv;
-    if (!(general ? invert_general(ATT, 6, inv) : invert_spd(ATT, 6, inv))) return false;
+    if (!(general ? invert_general(ATT, 6, inv) : invert_spd(ATT, 6, inv))) {
+      failed = true;
+      return;
+    }
     for (int a = 0; a < 6; ++a) {
       int fr = 2 * inner[a / 2] + a % 2;
-      for (int bb = 0; bb < 6; ++bb) {
-        double w = inv[(size_t)bb * 6 + a];
-        if (w == 0.0) continue;
-        for (auto& kv : AI[bb]) P[fr][kv.first] -= w * kv.second;
+      for (size_t j = 0; j < cols.size(); ++j) {
+        double s = 0.0;
+        for (int bb = 0; bb < 6; ++bb) s += inv[(size_t)bb * 6 + a] * AI[j * 6 + bb];
+        if (s != 0.0) add_to(fr, cols[j], -s);
       }
     }
   }
+  };
+  const int nth = Cl.nc >= 2048 ? (int)std::min(16u, std::max(1u, std::thread::hardware_concurrency())) : 1;
+  if (nth <= 1) {
+    cells(0, Cl.nc);
+  } else {
+    std::vector<std::thread> th;
+    const int chunk = (Cl.nc + nth - 1) / nth;
+    for (int i = 0; i < nth; ++i) th.emplace_back(cells, i * chunk, std::min(Cl.nc, (i + 1) * chunk));
+    for (auto& t : th) t.join();
+  }
+  if (failed) return false;
+  if (overflow) return false;
   Pc = CSR();
   Pc.n = nfd;
   Pc.rp.assign(1, 0);
+  Pc.ci.reserve((size_t)nfd * 14);
+  Pc.v.reserve((size_t)nfd * 14);
+  std::vector<std::pair<int, double>> row;
   for (int r = 0; r < nfd; ++r) {
-    for (auto& kv : P[r]) {
+    row.clear();
+    for (int e = 0; e < pn[r]; ++e) row.push_back({pc[(size_t)r * CAP + e], pv[(size_t)r * CAP + e]});
+    std::sort(row.begin(), row.end());
+    for (auto& kv : row) {
       if (kv.second == 0.0) continue;
       Pc.ci.push_back(kv.first);
       Pc.v.push_back(kv.second);
@@ -321,19 +391,20 @@ bool stabilised_transfer(const Level& Cl, const Level& Fl, const Averaging& Av, 
 }
 
 void csr_transpose(const CSR& A, int ncols, CSR& T) {
-  std::vector<std::vector<std::pair<int, double>>> cols(ncols);
-  for (int r = 0; r < A.n; ++r)
-    for (int q = A.rp[r]; q < A.rp[r + 1]; ++q) cols[A.ci[q]].push_back({r, A.v[q]});
   T = CSR();
   T.n = ncols;
-  T.rp.assign(1, 0);
-  for (int c = 0; c < ncols; ++c) {
-    for (auto& e : cols[c]) {
-      T.ci.push_back(e.first);
-      T.v.push_back(e.second);
+  T.rp.assign(ncols + 1, 0);
+  for (int c : A.ci) ++T.rp[c + 1];
+  for (int c = 0; c < ncols; ++c) T.rp[c + 1] += T.rp[c];
+  T.ci.resize(A.ci.size());
+  T.v.resize(A.v.size());
+  std::vector<int> next(T.rp.begin(), T.rp.end() - 1);
+  for (int r = 0; r < A.n; ++r)
+    for (int q = A.rp[r]; q < A.rp[r + 1]; ++q) {
+      const int at = next[A.ci[q]]++;
+      T.ci[at] = r;
+      T.v[at] = A.v[q];
     }
-    T.rp.push_back((int)T.ci.size());
-  }
 }
 
 void assemble_csr(const Level& L, const std::vector<double>& B, CSR& A) {
