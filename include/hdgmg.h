@@ -109,7 +109,7 @@ typedef struct {
 
 /* Defaults: m_p = m_h = 1, V-cycle, growth 2, rtol 1e-8, atol 1e-10,
  * max_it 500, uzawa_max 50, uzawa_tol 1e-10, coarse_dofs 2048,
- * stream_dofs 200000, vcycle_precision 0, oseen 0, restart 50. */
+ * stream_dofs 65536, vcycle_precision 0, oseen 0, restart 50. */
 void hdgmg_default_opts(hdgmg_opts* opts);
 
 #define HDGMG_MAX_UZAWA 64

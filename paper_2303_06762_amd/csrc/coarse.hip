@@ -189,7 +189,68 @@ __global__ void __launch_bounds__(CT) k_coarse_cycle(const CoarseLevel* __restri
   }
 }
 
+// One colour phase of record-based block Gauss-Seidel: a workgroup per
+// patch-aligned batch, a thread per patch row.  Patches of one colour share
+// no cell, so the rows a batch reads are never written by another batch of
+// the same launch.
+template <int NS, typename TS>
+__global__ void __launch_bounds__(GS_REC_THREADS)
+    k_gs_records(const unsigned* __restrict__ key, const unsigned* __restrict__ col, const TS* __restrict__ val,
+                 const TS* __restrict__ ainv, int nit, int nsm, const int* __restrict__ bitem, int b0,
+                 double* __restrict__ u, const double* __restrict__ g) {
+  __shared__ double res[GS_REC_THREADS + NS];
+  const int tid = threadIdx.x;
+  const int b = b0 + blockIdx.x;
+  const int t = bitem[b] + tid;
+  const bool on = t < bitem[b + 1];
+  if (tid < NS) res[GS_REC_THREADS + tid] = 0.0;
+  unsigned k = 0;
+  double r = 0.0;
+  if (on) {
+    k = key[t];
+    r = g[k & 0xffff];
+#pragma unroll
+    for (int q = 0; q < COARSE_NNZ / 2; ++q) {
+      const unsigned c = col[q * nit + t];
+      r -= (double)val[(2 * q) * nit + t] * u[c & 0xffff];
+      r -= (double)val[(2 * q + 1) * nit + t] * u[c >> 16];
+    }
+  }
+  res[tid] = on ? r : 0.0;
+  __syncthreads();
+  if (on) {
+    const int base = tid - (int)(k >> 16);
+    double d = 0.0;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) d += (j < nsm ? (double)ainv[j * nit + t] : 0.0) * res[base + j];
+    u[k & 0xffff] += d;
+  }
+}
+
+template <typename TS>
+void gs_records_t(hipStream_t st, const unsigned* key, const unsigned* col, const TS* val, const TS* ainv, int nit,
+                  int nsm, const int* bitem, int b0, int nb, double* u, const double* g) {
+  if (nsm <= 12)
+    hipLaunchKernelGGL((k_gs_records<12, TS>), dim3(nb), dim3(GS_REC_THREADS), 0, st, key, col, val, ainv, nit, nsm,
+                       bitem, b0, u, g);
+  else if (nsm <= 16)
+    hipLaunchKernelGGL((k_gs_records<16, TS>), dim3(nb), dim3(GS_REC_THREADS), 0, st, key, col, val, ainv, nit, nsm,
+                       bitem, b0, u, g);
+  else
+    hipLaunchKernelGGL((k_gs_records<32, TS>), dim3(nb), dim3(GS_REC_THREADS), 0, st, key, col, val, ainv, nit, nsm,
+                       bitem, b0, u, g);
+}
+
 }  // namespace
+
+void launch_gs_records(hipStream_t st, const unsigned* key, const unsigned* col, const void* val, const void* ainv,
+                       int nit, int nsm, const int* bitem, int b0, int nb, double* u, const double* g, int f32) {
+  if (nb <= 0) return;
+  if (f32)
+    gs_records_t<float>(st, key, col, (const float*)val, (const float*)ainv, nit, nsm, bitem, b0, nb, u, g);
+  else
+    gs_records_t<double>(st, key, col, (const double*)val, (const double*)ainv, nit, nsm, bitem, b0, nb, u, g);
+}
 
 template <typename TS>
 void coarse_t(hipStream_t st, const CoarseLevel* Ls, int top, int m_top, int growth, int q, const TS* inv0,

@@ -51,6 +51,15 @@ struct DevLevel {
   std::vector<int> colour_ptr;
   double* nu = nullptr;  // per cell
   double *u = nullptr, *g = nullptr, *r = nullptr;  // multigrid vectors
+  // record-based Gauss-Seidel (launched lowest-order levels): patch-row
+  // records in the V-cycle's storage, batches per colour
+  bool rec = false;
+  unsigned *rk = nullptr, *rc = nullptr;
+  const void *rv = nullptr, *ra = nullptr;
+  int* rbitem = nullptr;
+  std::vector<int> rcb;
+  int rnit = 0, rnsm = 0;
+  std::vector<double> rec_bytes;
   // lowest-order wind (Oseen): facet fluxes and RT0 coefficients per cell
   double* flux = nullptr;   // [nint]
   double* wcoef = nullptr;  // [nc][3]
@@ -465,6 +474,7 @@ hdgmg_status upload_f32(hdgmg_ctx* ctx, float** p, const std::vector<T>& h) {
 // the order-k level) in the storage the V-cycle reads.
 double phase_bytes(const hdgmg_ctx* ctx, const DevLevel& D, int level, int c) {
   if (D.fast) return D.bytes_cell_vc + D.bytes_relax_vc[c];
+  if (D.rec) return D.rec_bytes[c];
   const double scale = D.f32 ? 0.5 : 1.0;  // operator words dominate the phase bytes
   return scale * (level < 0 ? ctx->relax_bytes[c] : ctx->smooth_bytes[level][c]);
 }
@@ -487,6 +497,11 @@ void sweep(hdgmg_ctx* ctx, DevLevel& D, double* x, const double* b, bool forward
       else
         launch_patch_relax<double>(ctx->st, 2 * D.m, D.npc[c], D.pfc[c], D.Ppc[c], b, D.yF, x);
       kt_end(ctx, level < 0 ? 0 : 2, t, D.bytes_relax_vc[c]);
+    } else if (D.rec) {
+      int t = kt_begin(ctx, 2);
+      launch_gs_records(ctx->st, D.rk, D.rc, D.rv, D.ra, D.rnit, D.rnsm, D.rbitem, D.rcb[c], D.rcb[c + 1] - D.rcb[c],
+                        x, b, D.f32 ? 1 : 0);
+      kt_end(ctx, 2, t, phase_bytes(ctx, D, level, c));
     } else {
       const int cls = level < 0 ? 0 : 2;
       int t = kt_begin(ctx, cls);
@@ -868,6 +883,112 @@ hdgmg_status build_transfers(hdgmg_ctx* ctx) {
 // Descriptors of the levels handled by the single-workgroup coarse kernel:
 // per patch row its padded residual row (from the assembled operator) and its
 // row of the patch inverse (host FP64 Cholesky), structure-of-arrays.
+// Patch-row records of a lowest-order level (structure-of-arrays over
+// items, entry e of item t at [e * nit + t]): the unknown and its row inside
+// the patch, the padded residual row (16-bit column pairs) and the row of the
+// patch inverse; items colour by colour in patch-aligned batches of at most
+// max_items.  Also the padded residual rows per unknown.
+struct LevelRecords {
+  int n = 0, nit = 0, nsm = 0;
+  std::vector<unsigned> key, col;
+  std::vector<double> val, ainv;
+  std::vector<int> cb, bitem, bwd;
+  std::vector<int> rw_col;
+  std::vector<double> rw_val;
+};
+
+hdgmg_status level_records(hdgmg_ctx* ctx, int l, int max_items, LevelRecords& R) {
+  const Level& L = ctx->lv[l];
+  const int n = 2 * L.nint;
+  R = LevelRecords();
+  R.n = n;
+  if (n > 65535) {
+    ctx->err = "level too large for 16-bit record indices";
+    return HDGMG_EMESH;
+  }
+  CSR A;
+  assemble_csr(L, ctx->hostB[l], A);
+  R.rw_col.assign((size_t)COARSE_NNZ * n, 0);
+  R.rw_val.assign((size_t)COARSE_NNZ * n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    int nz = A.rp[i + 1] - A.rp[i];
+    if (nz > COARSE_NNZ) {
+      ctx->err = "lowest-order row with more than 10 entries";
+      return HDGMG_EMESH;
+    }
+    for (int k = 0; k < nz; ++k) {
+      R.rw_col[(size_t)k * n + i] = A.ci[A.rp[i] + k];
+      R.rw_val[(size_t)k * n + i] = A.v[A.rp[i] + k];
+    }
+  }
+  const int nsm = 2 * L.max_patch_facets;
+  R.nsm = nsm;
+  R.cb.assign(1, 0);
+  R.bitem.assign(1, 0);
+  std::vector<int> idof, iloc;
+  std::vector<double> irow;  // [item][nsm]
+  for (int c = 0; c < L.ncol; ++c) {
+    for (int p = L.colour_ptr[c]; p < L.colour_ptr[c + 1]; ++p) {
+      int f0 = L.patch_facet_ptr[p], nfp = L.patch_facet_ptr[p + 1] - f0;
+      int ns = 2 * nfp;
+      std::vector<int> dofs(ns);
+      for (int a = 0; a < nfp; ++a)
+        for (int comp = 0; comp < 2; ++comp) dofs[2 * a + comp] = 2 * L.patch_facets[f0 + a] + comp;
+      std::vector<double> Ass((size_t)ns * ns, 0.0), inv;
+      for (int i = 0; i < ns; ++i)
+        for (int q = A.rp[dofs[i]]; q < A.rp[dofs[i] + 1]; ++q)
+          for (int j = 0; j < ns; ++j)
+            if (A.ci[q] == dofs[j]) Ass[(size_t)i * ns + j] = A.v[q];
+      if (!(ctx->opts.oseen ? invert_general(Ass, ns, inv) : invert_spd(Ass, ns, inv))) {
+        ctx->err = "singular patch block on a lowest-order level";
+        return HDGMG_ENONFINITE;
+      }
+      if ((int)idof.size() - R.bitem.back() + ns > max_items) R.bitem.push_back((int)idof.size());
+      for (int i = 0; i < ns; ++i) {
+        idof.push_back(dofs[i]);
+        iloc.push_back(i);
+        for (int j = 0; j < nsm; ++j) irow.push_back(j < ns ? inv[(size_t)j * ns + i] : 0.0);  // row i
+      }
+    }
+    if ((int)idof.size() > R.bitem.back()) R.bitem.push_back((int)idof.size());
+    R.cb.push_back((int)R.bitem.size() - 1);
+  }
+  const int nit = (int)idof.size();
+  R.nit = nit;
+  R.key.resize(nit);
+  R.col.resize((size_t)(COARSE_NNZ / 2) * nit);
+  R.val.resize((size_t)COARSE_NNZ * nit);
+  R.ainv.resize((size_t)std::max(nsm, 1) * nit);
+  for (int t = 0; t < nit; ++t) {
+    R.key[t] = (unsigned)idof[t] | ((unsigned)iloc[t] << 16);
+    for (int k = 0; k < COARSE_NNZ; ++k) R.val[(size_t)k * nit + t] = R.rw_val[(size_t)k * n + idof[t]];
+    for (int k = 0; k < COARSE_NNZ / 2; ++k)
+      R.col[(size_t)k * nit + t] = (unsigned)R.rw_col[(size_t)(2 * k) * n + idof[t]] |
+                                   ((unsigned)R.rw_col[(size_t)(2 * k + 1) * n + idof[t]] << 16);
+    for (int j = 0; j < nsm; ++j) R.ainv[(size_t)j * nit + t] = irow[(size_t)t * nsm + j];
+  }
+  for (int c = L.ncol - 1; c >= 0; --c)
+    for (int bb = R.cb[c]; bb < R.cb[c + 1]; ++bb) R.bwd.push_back(bb);
+  return HDGMG_OK;
+}
+
+// Upload a float or double copy of host values (the V-cycle's storage).
+hdgmg_status upload_vals(hdgmg_ctx* ctx, const std::vector<double>& h, const void** out) {
+  if (ctx->opts.vcycle_precision == 1) {
+    float* tf;
+    TRY(upload_f32(ctx, &tf, h));
+    *out = tf;
+  } else {
+    double* td;
+    TRY(upload(ctx, &td, h));
+    *out = td;
+  }
+  return HDGMG_OK;
+}
+
+// Descriptors of the levels handled by the single-workgroup coarse kernel:
+// per patch row its padded residual row (from the assembled operator) and its
+// row of the patch inverse (host FP64 factorisation), structure-of-arrays.
 hdgmg_status build_coarse(hdgmg_ctx* ctx) {
   ctx->Lc = -1;
   if (ctx->opts.coarse_dofs <= 0) return HDGMG_OK;
@@ -897,112 +1018,34 @@ hdgmg_status build_coarse(hdgmg_ctx* ctx) {
     C.u_glob = D.u;
     C.g_glob = D.g;
     if (l == 0) continue;
-    CSR A;
-    assemble_csr(L, ctx->hostB[l], A);
-    // per-unknown padded rows
-    std::vector<int> rw_col((size_t)COARSE_NNZ * n, 0);
-    std::vector<double> rw_val((size_t)COARSE_NNZ * n, 0.0);
-    for (int i = 0; i < n; ++i) {
-      int nz = A.rp[i + 1] - A.rp[i];
-      if (nz > COARSE_NNZ) {
-        ctx->err = "lowest-order row with more than 10 entries";
-        return HDGMG_EMESH;
-      }
-      for (int k = 0; k < nz; ++k) {
-        rw_col[(size_t)k * n + i] = A.ci[A.rp[i] + k];
-        rw_val[(size_t)k * n + i] = A.v[A.rp[i] + k];
-      }
-    }
-    // items colour by colour, batches aligned to patches
-    int nsm = 2 * L.max_patch_facets;
-    std::vector<int> cb(1, 0), bitem(1, 0), idof, iloc;
-    std::vector<std::vector<double>> irow;  // inverse row per item
-    for (int c = 0; c < L.ncol; ++c) {
-      for (int p = L.colour_ptr[c]; p < L.colour_ptr[c + 1]; ++p) {
-        int f0 = L.patch_facet_ptr[p], nfp = L.patch_facet_ptr[p + 1] - f0;
-        int ns = 2 * nfp;
-        std::vector<int> dofs(ns);
-        for (int a = 0; a < nfp; ++a)
-          for (int comp = 0; comp < 2; ++comp) dofs[2 * a + comp] = 2 * L.patch_facets[f0 + a] + comp;
-        std::vector<double> Ass((size_t)ns * ns, 0.0), inv;
-        for (int i = 0; i < ns; ++i)
-          for (int q = A.rp[dofs[i]]; q < A.rp[dofs[i] + 1]; ++q)
-            for (int j = 0; j < ns; ++j)
-              if (A.ci[q] == dofs[j]) Ass[(size_t)i * ns + j] = A.v[q];
-        if (!(ctx->opts.oseen ? invert_general(Ass, ns, inv) : invert_spd(Ass, ns, inv))) {
-          ctx->err = "singular patch block on a coarse level";
-          return HDGMG_ENONFINITE;
-        }
-        if ((int)idof.size() - bitem.back() + ns > COARSE_THREADS) bitem.push_back((int)idof.size());
-        for (int i = 0; i < ns; ++i) {
-          idof.push_back(dofs[i]);
-          iloc.push_back(i);
-          std::vector<double> row(nsm, 0.0);
-          for (int j = 0; j < ns; ++j) row[j] = inv[(size_t)j * ns + i];  // row i (inv column-major)
-          irow.push_back(row);
-        }
-      }
-      if ((int)idof.size() > bitem.back()) bitem.push_back((int)idof.size());
-      cb.push_back((int)bitem.size() - 1);
-    }
-    const int nit = (int)idof.size();
-    if (n > 65535) {
-      ctx->err = "coarse level too large for 16-bit indices";
-      return HDGMG_EMESH;
-    }
-    std::vector<unsigned> it_key(nit), it_col((size_t)(COARSE_NNZ / 2) * nit);
-    std::vector<double> it_val((size_t)COARSE_NNZ * nit), it_ainv((size_t)std::max(nsm, 1) * nit);
-    for (int t = 0; t < nit; ++t) {
-      it_key[t] = (unsigned)idof[t] | ((unsigned)iloc[t] << 16);
-      for (int k = 0; k < COARSE_NNZ; ++k) it_val[(size_t)k * nit + t] = rw_val[(size_t)k * n + idof[t]];
-      for (int k = 0; k < COARSE_NNZ / 2; ++k)
-        it_col[(size_t)k * nit + t] = (unsigned)rw_col[(size_t)(2 * k) * n + idof[t]] |
-                                      ((unsigned)rw_col[(size_t)(2 * k + 1) * n + idof[t]] << 16);
-      for (int j = 0; j < nsm; ++j) it_ainv[(size_t)j * nit + t] = irow[t][j];
-    }
+    LevelRecords R;
+    TRY(level_records(ctx, l, COARSE_THREADS, R));
     C.ncol = L.ncol;
-    C.nitems = nit;
-    C.ns_max = nsm;
-    C.nbatch = (int)bitem.size() - 1;
+    C.nitems = R.nit;
+    C.ns_max = R.nsm;
+    C.nbatch = (int)R.bitem.size() - 1;
     if (C.nbatch > COARSE_MAX_BATCH) {
       ctx->err = "coarse level has too many batches";
       return HDGMG_EMESH;
     }
-    std::vector<int> bwd;
-    for (int c = L.ncol - 1; c >= 0; --c)
-      for (int bb = cb[c]; bb < cb[c + 1]; ++bb) bwd.push_back(bb);
     int* ti;
-    double* td;
     unsigned* tu;
-    TRY(upload(ctx, &ti, bwd));
+    TRY(upload(ctx, &ti, R.bwd));
     C.bseq_bwd = ti;
-    TRY(upload(ctx, &tu, it_key));
+    TRY(upload(ctx, &tu, R.key));
     C.it_key = tu;
-    TRY(upload(ctx, &ti, cb));
+    TRY(upload(ctx, &ti, R.cb));
     C.cb_ptr = ti;
-    TRY(upload(ctx, &ti, bitem));
+    TRY(upload(ctx, &ti, R.bitem));
     C.bitem = ti;
-    TRY(upload(ctx, &tu, it_col));
+    TRY(upload(ctx, &tu, R.col));
     C.it_col = tu;
-    const bool f32 = ctx->opts.vcycle_precision == 1;
-    float* tf;
-    if (f32) {
-      TRY(upload_f32(ctx, &tf, it_val));
-      C.it_val = tf;
-      TRY(upload_f32(ctx, &tf, it_ainv));
-      C.it_ainv = tf;
-      TRY(upload_f32(ctx, &tf, rw_val));
-      C.rw_val = tf;
-    } else {
-      TRY(upload(ctx, &td, it_val));
-      C.it_val = td;
-      TRY(upload(ctx, &td, it_ainv));
-      C.it_ainv = td;
-      TRY(upload(ctx, &td, rw_val));
-      C.rw_val = td;
-    }
-    TRY(upload(ctx, &ti, rw_col));
+    TRY(upload_vals(ctx, R.val, &C.it_val));
+    TRY(upload_vals(ctx, R.ainv, &C.it_ainv));
+    TRY(upload_vals(ctx, R.rw_val, &C.rw_val));
+    TRY(upload(ctx, &ti, R.rw_col));
     C.rw_col = ti;
+    const bool f32 = ctx->opts.vcycle_precision == 1;
     const DevTransfer& T = ctx->tr[l];
     C.R_rp = T.R_rp;
     C.R_ci = T.R_ci;
@@ -1019,6 +1062,35 @@ hdgmg_status build_coarse(hdgmg_ctx* ctx) {
   ctx->coarse_lds = off;
   ctx->coarse_ns = nsmax;
   ctx->Lc = Lc;
+  return HDGMG_OK;
+}
+
+// Record-based Gauss-Seidel for the launched lowest-order levels that are
+// not streamed (see k_gs_records): patch-aligned batches of 256 items.
+hdgmg_status build_record_levels(hdgmg_ctx* ctx) {
+  for (int l = std::max(ctx->Lc + 1, 1); l < ctx->J; ++l) {
+    DevLevel& D = ctx->cr[l];
+    D.rec = false;
+    const Level& L = ctx->lv[l];
+    if (D.fast || 2 * L.nint > 65535 || 2 * L.max_patch_facets > 32) continue;
+    LevelRecords R;
+    TRY(level_records(ctx, l, GS_REC_THREADS, R));
+    TRY(upload(ctx, &D.rk, R.key));
+    TRY(upload(ctx, &D.rc, R.col));
+    TRY(upload_vals(ctx, R.val, &D.rv));
+    TRY(upload_vals(ctx, R.ainv, &D.ra));
+    TRY(upload(ctx, &D.rbitem, R.bitem));
+    D.rcb = R.cb;
+    D.rnit = R.nit;
+    D.rnsm = R.nsm;
+    const double ws = ctx->opts.vcycle_precision == 1 ? 4.0 : 8.0;
+    D.rec_bytes.assign(L.ncol, 0.0);
+    for (int c = 0; c < L.ncol; ++c) {
+      const double items = R.bitem[R.cb[c + 1]] - R.bitem[R.cb[c]];
+      D.rec_bytes[c] = items * (4.0 + 4.0 * (COARSE_NNZ / 2) + ws * (COARSE_NNZ + R.nsm) + 8.0 * (COARSE_NNZ + 2));
+    }
+    D.rec = true;
+  }
   return HDGMG_OK;
 }
 
@@ -1108,6 +1180,7 @@ hdgmg_status assemble_levels(hdgmg_ctx* ctx) {
     TRY(make_f32(ctx, D));
   }
   TRY(build_coarse(ctx));
+  TRY(build_record_levels(ctx));
   HIPC(hipStreamSynchronize(ctx->st));
   return HDGMG_OK;
 }
@@ -1128,7 +1201,7 @@ void hdgmg_default_opts(hdgmg_opts* o) {
   o->uzawa_max = 50;
   o->uzawa_tol = 1e-10;
   o->coarse_dofs = 2048;
-  o->stream_dofs = 200000;
+  o->stream_dofs = 65536;
   o->vcycle_precision = 0;
   o->oseen = 0;
   o->restart = 50;
