@@ -408,8 +408,12 @@ void csr_transpose(const CSR& A, int ncols, CSR& T) {
 }
 
 void assemble_csr(const Level& L, const std::vector<double>& B, CSR& A) {
+  // a lowest-order unknown couples with the unknowns of the facets of its two
+  // cells: at most 10 columns per row
+  constexpr int CAP = 10;
   const int n = 2 * L.nint;
-  std::vector<std::map<int, double>> rows(n);
+  std::vector<int> ci((size_t)n * CAP), cnt(n, 0);
+  std::vector<double> cv((size_t)n * CAP);
   for (int c = 0; c < L.nc; ++c)
     for (int i1 = 0; i1 < 3; ++i1) {
       int f1 = L.cell_dofs[3 * c + i1];
@@ -418,15 +422,32 @@ void assemble_csr(const Level& L, const std::vector<double>& B, CSR& A) {
         int f2 = L.cell_dofs[3 * c + i2];
         if (f2 < 0) continue;
         for (int a = 0; a < 2; ++a)
-          for (int b = 0; b < 2; ++b)
-            rows[2 * f1 + a][2 * f2 + b] += B[(size_t)c * 36 + (2 * i1 + a) * 6 + 2 * i2 + b];
+          for (int b = 0; b < 2; ++b) {
+            const int r = 2 * f1 + a, col = 2 * f2 + b;
+            const double v = B[(size_t)c * 36 + (2 * i1 + a) * 6 + 2 * i2 + b];
+            int* rc = &ci[(size_t)r * CAP];
+            double* rv = &cv[(size_t)r * CAP];
+            int e = 0;
+            while (e < cnt[r] && rc[e] != col) ++e;
+            if (e == cnt[r]) {
+              if (e == CAP) continue;  // cannot happen on a conforming triangulation
+              rc[e] = col;
+              rv[e] = 0.0;
+              ++cnt[r];
+            }
+            rv[e] += v;
+          }
       }
     }
   A = CSR();
   A.n = n;
   A.rp.assign(1, 0);
+  std::vector<std::pair<int, double>> row;
   for (int r = 0; r < n; ++r) {
-    for (auto& kv : rows[r]) {
+    row.clear();
+    for (int e = 0; e < cnt[r]; ++e) row.push_back({ci[(size_t)r * CAP + e], cv[(size_t)r * CAP + e]});
+    std::sort(row.begin(), row.end());
+    for (auto& kv : row) {
       A.ci.push_back(kv.first);
       A.v.push_back(kv.second);
     }
