@@ -263,7 +263,7 @@ HDI int element_local(const QuadTables& Q, const CellGeom& g, double nu, double 
                       double eps_inv, int mode, const double* f, const double* lam,
                       double p0, WS w, double* out, const double* f2 = nullptr,
                       const double* lam2 = nullptr, const ConvTables* CT = nullptr,
-                      const double* wc = nullptr) {
+                      const double* wc = nullptr, const WS* fac = nullptr) {
   const Dims D = dims_of(Q.k);
   const int nP = D.nP, na = D.na, nz = D.nz, m = D.m, nK = D.nK, nN = D.nN, nkkt = D.nkkt;
   long o = 0;
@@ -495,6 +495,18 @@ HDI int element_local(const QuadTables& Q, const CellGeom& g, double nu, double 
         for (int c = j + 1; c < nkkt; ++c) Kk[(long)i * nkkt + c] -= l * Kk[(long)j * nkkt + c];
     }
   }
+  // ---- factors kept for later loads and recoveries (element_cached)
+  if (fac && mode == EL_CONDENSE) {
+    const WS& Fo = *fac;
+    long o2 = 0;
+    for (long i = 0; i < (long)nkkt * nkkt; ++i) Fo[o2++] = Kk[i];
+    for (int i = 0; i < nkkt; ++i) Fo[o2++] = piv[i];
+    for (int t = 0; t < 3 * m; ++t)
+      for (int a = 0; a < na; ++a) Fo[o2++] = H[(long)(na + t) * nz + a];  // H_ta (test t, trial a)
+    for (int a = 0; a < na; ++a)
+      for (int t = 0; t < 3 * m; ++t) Fo[o2++] = H[(long)a * nz + na + t];  // H_at
+    for (int r = 0; r < nP; ++r) Fo[o2++] = mean[r];
+  }
   // ---- right-hand sides
   int ncol = mode == EL_CONDENSE ? nK : mode == EL_GRADNU ? 2 : 1;
   for (long i = 0; i < (long)nkkt * ncol; ++i) Bx[i] = 0.0;
@@ -621,6 +633,95 @@ HDI int element_local(const QuadTables& Q, const CellGeom& g, double nu, double 
     }
   }
   return 0;
+}
+
+// Words per cell of the factors element_local keeps at condensation.
+HDI long element_fac_size(int k) {
+  const Dims D = dims_of(k);
+  return (long)D.nkkt * D.nkkt + D.nkkt + 6L * D.m * D.na + D.nP;
+}
+// Workspace of element_cached (doubles per cell).
+HDI long element_cached_ws_size(int k) {
+  const Dims D = dims_of(k);
+  return (long)D.na + D.nkkt;
+}
+
+// EL_LOAD / EL_RECOVER from the factors kept by element_local(EL_CONDENSE):
+// the same local solve with the LU factors of the cell's KKT matrix, so only
+// the source term and two triangular solves are computed.  Inputs and
+// outputs as element_local.
+HDI void element_cached(const QuadTables& Q, const CellGeom& g, int mode, const double* f, const double* lam,
+                        double p0, WS fac, WS w, double* out) {
+  const Dims D = dims_of(Q.k);
+  const int nP = D.nP, na = D.na, m = D.m, nK = D.nK, nN = D.nN, nkkt = D.nkkt;
+  const long oK = 0, oP = (long)nkkt * nkkt, oHta = oP + nkkt, oHat = oHta + 3L * m * na, oMean = oHat + 3L * m * na;
+  WS F{w.p, w.s};
+  WS Bx{w.p + (long)na * w.s, w.s};
+  double u[2 * 40], gr[4 * 40], mono[16];
+  for (int a = 0; a < na; ++a) F[a] = 0.0;
+  for (int q = 0; q < Q.nq; ++q) {
+    double x1 = Q.xi[q][0], x2 = Q.xi[q][1];
+    double xp[2] = {g.Xs0[0] + g.J[0][0] * x1 + g.J[0][1] * x2, g.Xs0[1] + g.J[1][0] * x1 + g.J[1][1] * x2};
+    double wt = Q.wq[q] * g.area;
+    rt_basis(D, g, x1, x2, xp, u, gr, mono);
+    for (int a = 0; a < na; ++a) F[a] += wt * (f[2 * q] * u[2 * a] + f[2 * q + 1] * u[2 * a + 1]);
+  }
+  for (int i = 0; i < nkkt; ++i) Bx[i] = i < na ? F[i] : 0.0;
+  if (mode == EL_RECOVER) {
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < m; ++j) {
+        Bx[na + i * m + j] += lam[(i * 2 + 0) * m + j];
+        const double ct = lam[(i * 2 + 1) * m + j];
+        for (int a = 0; a < na; ++a) Bx[a] -= fac[oHat + (long)a * 3 * m + i * m + j] * ct;
+      }
+  }
+  for (int j = 0; j < nkkt; ++j) {
+    const int pr = (int)fac[oP + j];
+    if (pr != j) {
+      double t = Bx[j];
+      Bx[j] = Bx[pr];
+      Bx[pr] = t;
+    }
+  }
+  for (int i = 0; i < nkkt; ++i) {
+    double s = Bx[i];
+    for (int p = 0; p < i; ++p) s -= fac[oK + (long)i * nkkt + p] * Bx[p];
+    Bx[i] = s;
+  }
+  for (int i = nkkt - 1; i >= 0; --i) {
+    double s = Bx[i];
+    for (int p = i + 1; p < nkkt; ++p) s -= fac[oK + (long)i * nkkt + p] * Bx[p];
+    Bx[i] = s / fac[oK + (long)i * nkkt + i];
+  }
+  if (mode == EL_LOAD) {
+    for (int l1 = 0; l1 < nK; ++l1) {
+      const int i = l1 / (2 * m), c = (l1 / m) % 2, j = l1 % m;
+      double btx;
+      if (c == 0) {
+        btx = Bx[na + i * m + j];
+      } else {
+        btx = 0.0;
+        for (int a = 0; a < na; ++a) btx -= fac[oHta + (long)(i * m + j) * na + a] * Bx[a];
+      }
+      out[l1] = btx;
+    }
+    return;
+  }
+  for (int q = 0; q < Q.nq; ++q) {
+    double x1 = Q.xi[q][0], x2 = Q.xi[q][1];
+    double xp[2] = {g.Xs0[0] + g.J[0][0] * x1 + g.J[0][1] * x2, g.Xs0[1] + g.J[1][0] * x1 + g.J[1][1] * x2};
+    rt_basis(D, g, x1, x2, xp, u, gr, mono);
+    double ux = 0.0, uy = 0.0;
+    for (int a = 0; a < na; ++a) {
+      ux += Bx[a] * u[2 * a];
+      uy += Bx[a] * u[2 * a + 1];
+    }
+    double p = p0;
+    for (int r = 1; r < nP; ++r) p -= Bx[na + nN + r - 1] * (mono[r] - fac[oMean + r]);
+    out[2 * q] = ux;
+    out[2 * q + 1] = uy;
+    out[2 * Q.nq + q] = p;
+  }
 }
 
 // Coefficients in this cell's RT_k basis of a velocity field given at the

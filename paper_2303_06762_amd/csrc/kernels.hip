@@ -21,8 +21,10 @@ __global__ void k_condense(ElemLevel E, int c0, int nbatch, double* ws, double* 
   cell_geom(E.X, E.cells + 3 * c, g);
   const int nK = 6 * (E.Q.k + 1);
   double nuc = E.nu_per_cell ? E.nu[c] : E.nu[0];
+  const WS fv{E.fac ? E.fac + c : nullptr, E.nc};
   int rc = element_local(E.Q, g, nuc, E.beta, E.eps_inv, EL_CONDENSE, nullptr, nullptr, 0.0, WS{ws + t, nbatch},
-                         S + (long)c * nK * nK, nullptr, nullptr, E.CT, E.wcoef ? E.wcoef + (long)c * E.na : nullptr);
+                         S + (long)c * nK * nK, nullptr, nullptr, E.CT, E.wcoef ? E.wcoef + (long)c * E.na : nullptr,
+                         E.fac ? &fv : nullptr);
   if (rc) atomicOr(status, 1);
 }
 
@@ -45,10 +47,15 @@ __global__ void k_load(ElemLevel E, int c0, int nbatch, const double* __restrict
   const int nK = 6 * (E.Q.k + 1);
   double nuc = E.nu_per_cell ? E.nu[c] : E.nu[0];
   double* out = gK + (long)c * nK;
-  int rc = element_local(E.Q, g, nuc, E.beta, 0.0, EL_LOAD, f + (long)c * E.Q.nq * 2, nullptr, 0.0,
-                         WS{ws + t, nbatch}, out, nullptr, nullptr, E.CT,
-                         E.wcoef ? E.wcoef + (long)c * E.na : nullptr);
-  if (rc) atomicOr(status, 1);
+  if (E.fac) {
+    element_cached(E.Q, g, EL_LOAD, f + (long)c * E.Q.nq * 2, nullptr, 0.0, WS{E.fac + c, E.nc},
+                   WS{ws + t, nbatch}, out);
+  } else {
+    int rc = element_local(E.Q, g, nuc, E.beta, 0.0, EL_LOAD, f + (long)c * E.Q.nq * 2, nullptr, 0.0,
+                           WS{ws + t, nbatch}, out, nullptr, nullptr, E.CT,
+                           E.wcoef ? E.wcoef + (long)c * E.na : nullptr);
+    if (rc) atomicOr(status, 1);
+  }
   if (E.bdl) {
     double lb[6 * (KMAX + 1)];
     boundary_local(E, c, lb);
@@ -80,10 +87,15 @@ __global__ void k_recover(ElemLevel E, int c0, int nbatch, const double* __restr
   }
   double out[3 * NQ_MAX];
   double nuc = E.nu_per_cell ? E.nu[c] : E.nu[0];
-  int rc = element_local(E.Q, g, nuc, E.beta, 0.0, EL_RECOVER, f + (long)c * E.Q.nq * 2, lk, p0[c],
-                         WS{ws + t, nbatch}, out, nullptr, nullptr, E.CT,
-                         E.wcoef ? E.wcoef + (long)c * E.na : nullptr);
-  if (rc) atomicOr(status, 1);
+  if (E.fac) {
+    element_cached(E.Q, g, EL_RECOVER, f + (long)c * E.Q.nq * 2, lk, p0[c], WS{E.fac + c, E.nc},
+                   WS{ws + t, nbatch}, out);
+  } else {
+    int rc = element_local(E.Q, g, nuc, E.beta, 0.0, EL_RECOVER, f + (long)c * E.Q.nq * 2, lk, p0[c],
+                           WS{ws + t, nbatch}, out, nullptr, nullptr, E.CT,
+                           E.wcoef ? E.wcoef + (long)c * E.na : nullptr);
+    if (rc) atomicOr(status, 1);
+  }
   for (int q = 0; q < E.Q.nq; ++q) {
     u[((long)c * E.Q.nq + q) * 2] = out[2 * q];
     u[((long)c * E.Q.nq + q) * 2 + 1] = out[2 * q + 1];

@@ -42,6 +42,9 @@ struct ElemLevel {
   int m;
   const double* bdl;        // [nc][3][m] prescribed tangential boundary values, or null
   const double* S;          // [nc][nK][nK] condensed blocks (the loads' boundary lift)
+  double* fac;              // kept local factors (element_fac_size per cell, element i
+                            // of cell c at fac[i * nc + c]), or null
+  int nc;
 };
 
 void launch_condense(hipStream_t st, const ElemLevel& E, int c0, int nbatch, double* ws, double* S, int* status);

@@ -166,6 +166,7 @@ struct hdgmg_ctx {
   ConvTables* CT0 = nullptr;
   bool has_wind = false;
   double* wcoef = nullptr;    // [n_cells][na] wind coefficients (order-k level)
+  double* fac = nullptr;      // kept local factors of the order-k cells (loads, recovery)
   // lowest-order cell blocks of every level on the host (transfers, coarse levels)
   std::vector<std::vector<double>> hostB;
   // tangential Dirichlet data on the finest boundary facets
@@ -1116,6 +1117,8 @@ ElemLevel elem_level(const hdgmg_ctx* ctx, const DevLevel& D, bool order_k, bool
   E.m = D.m;
   E.bdl = order_k && ctx->has_bd ? ctx->bdl : nullptr;
   E.S = D.S;
+  E.fac = order_k ? ctx->fac : nullptr;
+  E.nc = D.nc;
   return E;
 }
 
@@ -1362,6 +1365,7 @@ hdgmg_status hdgmg_setup(const hdgmg_mesh* mesh, int k, double beta, const doubl
   if ((s = dalloc(ctx, &ctx->gK, (size_t)LF.nc * 6 * (k + 1)))) return fail(s);
   if ((s = dalloc(ctx, &ctx->status, 1))) return fail(s);
   if ((s = dalloc(ctx, &ctx->statebuf, (size_t)(n + LF.nc)))) return fail(s);
+  if ((s = dalloc(ctx, &ctx->fac, (size_t)LF.nc * element_fac_size(k)))) return fail(s);
   // Uzawa geometry: per interior facet and side sigma|F|, per cell sigma|F| and |K|
   std::vector<double> fdiv(2 * (size_t)LF.nint), cdiv(3 * (size_t)LF.nc), area(LF.area);
   for (int i = 0; i < LF.nint; ++i) {
