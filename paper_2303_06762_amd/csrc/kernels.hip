@@ -362,6 +362,93 @@ __global__ void k_patch_inverse(LevelView L, const int* __restrict__ pc_ptr, con
   }
 }
 
+// The same inverses with one wavefront per patch: A_ss assembled in LDS
+// next to the identity, Gauss-Jordan elimination with partial pivoting
+// (lanes over columns, pivot search across lanes), inverse written
+// column-major.  For patches of at most PI_WAVE_NS unknowns.
+__device__ inline void wave_argmax(double& v, int& idx) {
+  for (int off = 32; off > 0; off >>= 1) {
+    double ov = __shfl_xor(v, off);
+    int oi = __shfl_xor(idx, off);
+    if (ov > v || (ov == v && oi < idx)) {
+      v = ov;
+      idx = oi;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(64) k_patch_inverse_wave(LevelView L, const int* __restrict__ pc_ptr,
+                                                           const int* __restrict__ pc, double* pinv, int* status) {
+  extern __shared__ double sm[];
+  const int p = blockIdx.x, lane = threadIdx.x;
+  const int m2 = 2 * L.m;
+  const int f0 = L.pf_ptr[p], nfp = L.pf_ptr[p + 1] - f0;
+  const int ns = nfp * m2, w = 2 * ns;
+  double* A = sm;              // [ns][2 ns]: A_ss | I
+  double* fct = sm + ns * w;   // [ns] elimination factors
+  for (int e = lane; e < ns * w; e += 64) {
+    const int i = e / w, c = e % w;
+    A[e] = (c - ns == i) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int q = pc_ptr[p]; q < pc_ptr[p + 1]; ++q) {
+    const int K = pc[q];
+    int pos[3];
+    for (int i = 0; i < 3; ++i) {
+      pos[i] = -1;
+      const int d = L.cell_dofs[3 * K + i];
+      for (int a = 0; a < nfp && d >= 0; ++a)
+        if (L.pf[f0 + a] == d) pos[i] = a;
+    }
+    const double* SK = L.S + (long)K * L.nK * L.nK;
+    for (int e = lane; e < L.nK * L.nK; e += 64) {
+      const int r = e / L.nK, c = e % L.nK;
+      const int i1 = r / m2, i2 = c / m2;
+      if (pos[i1] < 0 || pos[i2] < 0) continue;
+      A[(pos[i1] * m2 + r % m2) * w + pos[i2] * m2 + c % m2] += SK[e];
+    }
+    __syncthreads();
+  }
+  for (int j = 0; j < ns; ++j) {
+    double v = -1.0;
+    int idx = j;
+    for (int i = j + lane; i < ns; i += 64) {
+      const double a = fabs(A[i * w + j]);
+      if (a > v) {
+        v = a;
+        idx = i;
+      }
+    }
+    wave_argmax(v, idx);
+    if (!(v > 0.0)) {
+      if (lane == 0) atomicOr(status, 2);
+      return;
+    }
+    if (idx != j)
+      for (int c = lane; c < w; c += 64) {
+        const double t = A[j * w + c];
+        A[j * w + c] = A[idx * w + c];
+        A[idx * w + c] = t;
+      }
+    __syncthreads();
+    const double dinv = 1.0 / A[j * w + j];
+    __syncthreads();
+    for (int c = lane; c < w; c += 64) A[j * w + c] *= dinv;
+    for (int i = lane; i < ns; i += 64) fct[i] = i == j ? 0.0 : A[i * w + j];
+    __syncthreads();
+    for (int c = lane; c < w; c += 64) {
+      const double rj = A[j * w + c];
+      for (int i = 0; i < ns; ++i) A[i * w + c] -= fct[i] * rj;
+    }
+    __syncthreads();
+  }
+  double* out = pinv + L.pinv_off[p];
+  for (int e = lane; e < ns * ns; e += 64) {
+    const int c = e / ns, i = e % ns;
+    out[e] = A[i * w + ns + c];  // column c, row i
+  }
+}
+
 // Row (facet fi, local row rr) of A x: sum over the two cells of fi.
 template <typename TS>
 __device__ inline double row_dot(const LevelViewT<TS>& L, int fi, int rr, const double* __restrict__ x) {
@@ -694,6 +781,11 @@ void launch_cr_blocks(hipStream_t st, const double* X, const int* cells, int nc,
 void launch_patch_inverse(hipStream_t st, LevelView L, const int* pc_ptr, const int* pc, int npatch,
                           int max_ns, int general, double* ws, double* pinv, int* status) {
   if (npatch <= 0) return;
+  if (max_ns <= PI_WAVE_NS) {
+    const size_t shm = sizeof(double) * ((size_t)max_ns * 2 * max_ns + max_ns);
+    hipLaunchKernelGGL(k_patch_inverse_wave, dim3(npatch), dim3(64), shm, st, L, pc_ptr, pc, pinv, status);
+    return;
+  }
   hipLaunchKernelGGL(k_patch_inverse, dim3(nblk(npatch, 64)), dim3(64), 0, st, L, pc_ptr, pc, npatch, max_ns,
                      general, ws, pinv, status);
 }

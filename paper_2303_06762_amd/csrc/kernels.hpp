@@ -78,8 +78,11 @@ void launch_data_weight(hipStream_t st, const QuadTables& Q, const double* X, co
                         const double* in, int inverse, double* out);
 void launch_cr_blocks(hipStream_t st, const double* X, const int* cells, int nc,
                       const double* nu_cells, double beta, double eps_inv, double* A);
-// Inverses of the patch blocks A_ss (column-major): Cholesky, or LU with
-// partial pivoting when general != 0 (workspace max_ns^2 + max_ns per patch).
+// Inverses of the patch blocks A_ss (column-major).  Patches of at most
+// PI_WAVE_NS unknowns: a wavefront per patch, Gauss-Jordan with partial
+// pivoting in LDS; larger ones: a thread per patch, Cholesky or (general != 0)
+// LU with partial pivoting (workspace max_ns^2 + max_ns per patch).
+constexpr int PI_WAVE_NS = 60;
 void launch_patch_inverse(hipStream_t st, LevelView L, const int* pc_ptr, const int* pc,
                           int npatch, int max_ns, int general, double* ws, double* pinv, int* status);
 // y = alpha * A x + (b ? b : 0)
