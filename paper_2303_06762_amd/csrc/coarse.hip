@@ -32,18 +32,39 @@ struct Rec {
   TS ai[NS];
 };
 
+// Pair type of the record values (one 16- or 8-byte load per lane).
+template <typename TS>
+struct Pair;
+template <>
+struct Pair<double> {
+  using T = double2;
+};
+template <>
+struct Pair<float> {
+  using T = float2;
+};
+
 template <int NS, typename TS>
 __device__ inline void load_rec(const CoarseLevel& L, int t, Rec<NS, TS>& r) {
+  using P2 = typename Pair<TS>::T;
   const int nit = L.nitems;
-  const TS* val = (const TS*)L.it_val;
-  const TS* ainv = (const TS*)L.it_ainv;
+  const P2* val = (const P2*)L.it_val;
+  const P2* ainv = (const P2*)L.it_ainv;
   r.key = L.it_key[t];
 #pragma unroll
   for (int k = 0; k < COARSE_NNZ / 2; ++k) r.col[k] = L.it_col[k * nit + t];
 #pragma unroll
-  for (int k = 0; k < COARSE_NNZ; ++k) r.val[k] = val[k * nit + t];
+  for (int k = 0; k < COARSE_NNZ / 2; ++k) {
+    const P2 v = val[k * nit + t];
+    r.val[2 * k] = v.x;
+    r.val[2 * k + 1] = v.y;
+  }
 #pragma unroll
-  for (int j = 0; j < NS; ++j) r.ai[j] = j < L.ns_max ? ainv[j * nit + t] : (TS)0;
+  for (int j = 0; j < NS / 2; ++j) {
+    const P2 v = 2 * j < L.ns_max ? ainv[j * nit + t] : P2{(TS)0, (TS)0};
+    r.ai[2 * j] = v.x;
+    r.ai[2 * j + 1] = v.y;
+  }
 }
 
 // `sweeps` block Gauss-Seidel sweeps over the colours (forward or reversed),
@@ -206,14 +227,16 @@ __global__ void __launch_bounds__(GS_REC_THREADS)
   if (tid < NS) res[GS_REC_THREADS + tid] = 0.0;
   unsigned k = 0;
   double r = 0.0;
+  using P2 = typename Pair<TS>::T;
   if (on) {
     k = key[t];
     r = g[k & 0xffff];
 #pragma unroll
     for (int q = 0; q < COARSE_NNZ / 2; ++q) {
       const unsigned c = col[q * nit + t];
-      r -= (double)val[(2 * q) * nit + t] * u[c & 0xffff];
-      r -= (double)val[(2 * q + 1) * nit + t] * u[c >> 16];
+      const P2 v = ((const P2*)val)[q * nit + t];
+      r -= (double)v.x * u[c & 0xffff];
+      r -= (double)v.y * u[c >> 16];
     }
   }
   res[tid] = on ? r : 0.0;
@@ -222,7 +245,10 @@ __global__ void __launch_bounds__(GS_REC_THREADS)
     const int base = tid - (int)(k >> 16);
     double d = 0.0;
 #pragma unroll
-    for (int j = 0; j < NS; ++j) d += (j < nsm ? (double)ainv[j * nit + t] : 0.0) * res[base + j];
+    for (int j = 0; j < NS / 2; ++j) {
+      const P2 v = 2 * j < nsm ? ((const P2*)ainv)[j * nit + t] : P2{(TS)0, (TS)0};
+      d += (double)v.x * res[base + 2 * j] + (double)v.y * res[base + 2 * j + 1];
+    }
     u[k & 0xffff] += d;
   }
 }

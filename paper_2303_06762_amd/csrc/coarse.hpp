@@ -31,8 +31,8 @@ struct CoarseLevel {
   const unsigned* it_key;     // [nitems] unknown | (row inside its patch) << 16
   const unsigned* it_col;     // [COARSE_NNZ/2][nitems] residual row columns,
                               // two 16-bit indices per word
-  const void* it_val;         // [COARSE_NNZ][nitems] residual row: values
-  const void* it_ainv;        // [ns_max][nitems] row of the patch inverse
+  const void* it_val;         // [COARSE_NNZ/2][nitems][2] residual row values (pairs)
+  const void* it_ainv;        // [ns_max/2][nitems][2] row of the patch inverse (pairs)
   const int* rw_col;          // [COARSE_NNZ][n] rows of A for the residual
   const void* rw_val;
   const int* R_rp;            // restriction to level l-1 (CSR, its unknowns)

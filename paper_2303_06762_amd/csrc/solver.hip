@@ -885,7 +885,9 @@ hdgmg_status build_transfers(hdgmg_ctx* ctx) {
 // per patch row its padded residual row (from the assembled operator) and its
 // row of the patch inverse (host FP64 Cholesky), structure-of-arrays.
 // Patch-row records of a lowest-order level (structure-of-arrays over
-// items, entry e of item t at [e * nit + t]): the unknown and its row inside
+// items; keys and columns: entry e of item t at [e * nit + t]; values and
+// inverse rows in pairs, entries 2e and 2e+1 at [(e * nit + t) * 2 + 0, 1] so
+// that a lane reads both with one load): the unknown and its row inside
 // the patch, the padded residual row (16-bit column pairs) and the row of the
 // patch inverse; items colour by colour in patch-aligned batches of at most
 // max_items.  Also the padded residual rows per unknown.
@@ -962,11 +964,13 @@ hdgmg_status level_records(hdgmg_ctx* ctx, int l, int max_items, LevelRecords& R
   R.ainv.resize((size_t)std::max(nsm, 1) * nit);
   for (int t = 0; t < nit; ++t) {
     R.key[t] = (unsigned)idof[t] | ((unsigned)iloc[t] << 16);
-    for (int k = 0; k < COARSE_NNZ; ++k) R.val[(size_t)k * nit + t] = R.rw_val[(size_t)k * n + idof[t]];
+    // values in pairs: entries 2e, 2e+1 of item t at [(e * nit + t) * 2 + 0, 1]
+    for (int k = 0; k < COARSE_NNZ; ++k)
+      R.val[((size_t)(k / 2) * nit + t) * 2 + k % 2] = R.rw_val[(size_t)k * n + idof[t]];
     for (int k = 0; k < COARSE_NNZ / 2; ++k)
       R.col[(size_t)k * nit + t] = (unsigned)R.rw_col[(size_t)(2 * k) * n + idof[t]] |
                                    ((unsigned)R.rw_col[(size_t)(2 * k + 1) * n + idof[t]] << 16);
-    for (int j = 0; j < nsm; ++j) R.ainv[(size_t)j * nit + t] = irow[(size_t)t * nsm + j];
+    for (int j = 0; j < nsm; ++j) R.ainv[((size_t)(j / 2) * nit + t) * 2 + j % 2] = irow[(size_t)t * nsm + j];
   }
   for (int c = L.ncol - 1; c >= 0; --c)
     for (int bb = R.cb[c]; bb < R.cb[c + 1]; ++bb) R.bwd.push_back(bb);
