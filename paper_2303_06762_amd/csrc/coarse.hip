@@ -50,9 +50,14 @@ __device__ inline void load_rec(const CoarseLevel& L, int t, Rec<NS, TS>& r) {
   const int nit = L.nitems;
   const P2* val = (const P2*)L.it_val;
   const P2* ainv = (const P2*)L.it_ainv;
-  r.key = L.it_key[t];
-#pragma unroll
-  for (int k = 0; k < COARSE_NNZ / 2; ++k) r.col[k] = L.it_col[k * nit + t];
+  const uint4 m0 = L.it_meta[t];
+  const uint4 m1 = L.it_meta[nit + t];
+  r.key = m0.x;
+  r.col[0] = m0.y;
+  r.col[1] = m0.z;
+  r.col[2] = m0.w;
+  r.col[3] = m1.x;
+  r.col[4] = m1.y;
 #pragma unroll
   for (int k = 0; k < COARSE_NNZ / 2; ++k) {
     const P2 v = val[k * nit + t];
@@ -216,9 +221,9 @@ __global__ void __launch_bounds__(CT) k_coarse_cycle(const CoarseLevel* __restri
 // the same launch.
 template <int NS, typename TS>
 __global__ void __launch_bounds__(GS_REC_THREADS)
-    k_gs_records(const unsigned* __restrict__ key, const unsigned* __restrict__ col, const TS* __restrict__ val,
-                 const TS* __restrict__ ainv, int nit, int nsm, const int* __restrict__ bitem, int b0,
-                 double* __restrict__ u, const double* __restrict__ g) {
+    k_gs_records(const uint4* __restrict__ meta, const TS* __restrict__ val, const TS* __restrict__ ainv, int nit,
+                 int nsm, const int* __restrict__ bitem, int b0, double* __restrict__ u,
+                 const double* __restrict__ g) {
   __shared__ double res[GS_REC_THREADS + NS];
   const int tid = threadIdx.x;
   const int b = b0 + blockIdx.x;
@@ -229,11 +234,13 @@ __global__ void __launch_bounds__(GS_REC_THREADS)
   double r = 0.0;
   using P2 = typename Pair<TS>::T;
   if (on) {
-    k = key[t];
+    const uint4 m0 = meta[t], m1 = meta[nit + t];
+    const unsigned cols[COARSE_NNZ / 2] = {m0.y, m0.z, m0.w, m1.x, m1.y};
+    k = m0.x;
     r = g[k & 0xffff];
 #pragma unroll
     for (int q = 0; q < COARSE_NNZ / 2; ++q) {
-      const unsigned c = col[q * nit + t];
+      const unsigned c = cols[q];
       const P2 v = ((const P2*)val)[q * nit + t];
       r -= (double)v.x * u[c & 0xffff];
       r -= (double)v.y * u[c >> 16];
@@ -254,28 +261,29 @@ __global__ void __launch_bounds__(GS_REC_THREADS)
 }
 
 template <typename TS>
-void gs_records_t(hipStream_t st, const unsigned* key, const unsigned* col, const TS* val, const TS* ainv, int nit,
-                  int nsm, const int* bitem, int b0, int nb, double* u, const double* g) {
+void gs_records_t(hipStream_t st, const uint4* meta, const TS* val, const TS* ainv, int nit, int nsm,
+                  const int* bitem, int b0, int nb, double* u, const double* g) {
   if (nsm <= 12)
-    hipLaunchKernelGGL((k_gs_records<12, TS>), dim3(nb), dim3(GS_REC_THREADS), 0, st, key, col, val, ainv, nit, nsm,
+    hipLaunchKernelGGL((k_gs_records<12, TS>), dim3(nb), dim3(GS_REC_THREADS), 0, st, meta, val, ainv, nit, nsm,
                        bitem, b0, u, g);
   else if (nsm <= 16)
-    hipLaunchKernelGGL((k_gs_records<16, TS>), dim3(nb), dim3(GS_REC_THREADS), 0, st, key, col, val, ainv, nit, nsm,
+    hipLaunchKernelGGL((k_gs_records<16, TS>), dim3(nb), dim3(GS_REC_THREADS), 0, st, meta, val, ainv, nit, nsm,
                        bitem, b0, u, g);
   else
-    hipLaunchKernelGGL((k_gs_records<32, TS>), dim3(nb), dim3(GS_REC_THREADS), 0, st, key, col, val, ainv, nit, nsm,
+    hipLaunchKernelGGL((k_gs_records<32, TS>), dim3(nb), dim3(GS_REC_THREADS), 0, st, meta, val, ainv, nit, nsm,
                        bitem, b0, u, g);
 }
 
 }  // namespace
 
-void launch_gs_records(hipStream_t st, const unsigned* key, const unsigned* col, const void* val, const void* ainv,
-                       int nit, int nsm, const int* bitem, int b0, int nb, double* u, const double* g, int f32) {
+void launch_gs_records(hipStream_t st, const unsigned* meta, const void* val, const void* ainv, int nit, int nsm,
+                       const int* bitem, int b0, int nb, double* u, const double* g, int f32) {
   if (nb <= 0) return;
+  const uint4* m = (const uint4*)meta;
   if (f32)
-    gs_records_t<float>(st, key, col, (const float*)val, (const float*)ainv, nit, nsm, bitem, b0, nb, u, g);
+    gs_records_t<float>(st, m, (const float*)val, (const float*)ainv, nit, nsm, bitem, b0, nb, u, g);
   else
-    gs_records_t<double>(st, key, col, (const double*)val, (const double*)ainv, nit, nsm, bitem, b0, nb, u, g);
+    gs_records_t<double>(st, m, (const double*)val, (const double*)ainv, nit, nsm, bitem, b0, nb, u, g);
 }
 
 template <typename TS>

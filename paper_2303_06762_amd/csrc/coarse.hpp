@@ -28,9 +28,10 @@ struct CoarseLevel {
   const int* bitem;           // [nbatch+1] item range of each batch
                               // (<= COARSE_THREADS items, patch-aligned)
   const int* bseq_bwd;        // [nbatch] batches in reverse colour order
-  const unsigned* it_key;     // [nitems] unknown | (row inside its patch) << 16
-  const unsigned* it_col;     // [COARSE_NNZ/2][nitems] residual row columns,
-                              // two 16-bit indices per word
+  const uint4* it_meta;       // [2][nitems]: (key, cols01, cols23, cols45),
+                              // (cols67, cols89, 0, 0); key = unknown |
+                              // (row inside its patch) << 16, columns two
+                              // 16-bit indices per word
   const void* it_val;         // [COARSE_NNZ/2][nitems][2] residual row values (pairs)
   const void* it_ainv;        // [ns_max/2][nitems][2] row of the patch inverse (pairs)
   const int* rw_col;          // [COARSE_NNZ][n] rows of A for the residual
@@ -50,11 +51,11 @@ constexpr int GS_REC_THREADS = 256;
 
 // One colour phase of block Gauss-Seidel on a launched lowest-order level
 // from its patch-row records (the same structure-of-arrays record layout as
-// CoarseLevel: key, col, val, ainv over nit items; batches [b0, b0 + nb) of
+// CoarseLevel: meta, val, ainv over nit items; batches [b0, b0 + nb) of
 // bitem, patch-aligned, at most GS_REC_THREADS items): u += A_ss^-1 (g - A u)_s
 // for every patch of the colour.  f32: val and ainv are float, else double.
-void launch_gs_records(hipStream_t st, const unsigned* key, const unsigned* col, const void* val, const void* ainv,
-                       int nit, int nsm, const int* bitem, int b0, int nb, double* u, const double* g, int f32);
+void launch_gs_records(hipStream_t st, const unsigned* meta, const void* val, const void* ainv, int nit, int nsm,
+                       const int* bitem, int b0, int nb, double* u, const double* g, int f32);
 
 // u_top <- MG_h(top, g_top, u_top, m_top, q) with m(l-1) = growth m(l) on
 // levels 0..top (top <= the levels described by Ls); level 0 is solved with

@@ -54,7 +54,7 @@ struct DevLevel {
   // record-based Gauss-Seidel (launched lowest-order levels): patch-row
   // records in the V-cycle's storage, batches per colour
   bool rec = false;
-  unsigned *rk = nullptr, *rc = nullptr;
+  unsigned* rk = nullptr;  // [2][nit][4] meta words
   const void *rv = nullptr, *ra = nullptr;
   int* rbitem = nullptr;
   std::vector<int> rcb;
@@ -500,7 +500,7 @@ void sweep(hdgmg_ctx* ctx, DevLevel& D, double* x, const double* b, bool forward
       kt_end(ctx, level < 0 ? 0 : 2, t, D.bytes_relax_vc[c]);
     } else if (D.rec) {
       int t = kt_begin(ctx, 2);
-      launch_gs_records(ctx->st, D.rk, D.rc, D.rv, D.ra, D.rnit, D.rnsm, D.rbitem, D.rcb[c], D.rcb[c + 1] - D.rcb[c],
+      launch_gs_records(ctx->st, D.rk, D.rv, D.ra, D.rnit, D.rnsm, D.rbitem, D.rcb[c], D.rcb[c + 1] - D.rcb[c],
                         x, b, D.f32 ? 1 : 0);
       kt_end(ctx, 2, t, phase_bytes(ctx, D, level, c));
     } else {
@@ -885,7 +885,8 @@ hdgmg_status build_transfers(hdgmg_ctx* ctx) {
 // per patch row its padded residual row (from the assembled operator) and its
 // row of the patch inverse (host FP64 Cholesky), structure-of-arrays.
 // Patch-row records of a lowest-order level (structure-of-arrays over
-// items; keys and columns: entry e of item t at [e * nit + t]; values and
+// items; per item two 16-byte meta words (key, columns 0-2), (columns 3-4)
+// at [w][t]; values and
 // inverse rows in pairs, entries 2e and 2e+1 at [(e * nit + t) * 2 + 0, 1] so
 // that a lane reads both with one load): the unknown and its row inside
 // the patch, the padded residual row (16-bit column pairs) and the row of the
@@ -893,7 +894,7 @@ hdgmg_status build_transfers(hdgmg_ctx* ctx) {
 // max_items.  Also the padded residual rows per unknown.
 struct LevelRecords {
   int n = 0, nit = 0, nsm = 0;
-  std::vector<unsigned> key, col;
+  std::vector<unsigned> meta;
   std::vector<double> val, ainv;
   std::vector<int> cb, bitem, bwd;
   std::vector<int> rw_col;
@@ -958,18 +959,23 @@ hdgmg_status level_records(hdgmg_ctx* ctx, int l, int max_items, LevelRecords& R
   }
   const int nit = (int)idof.size();
   R.nit = nit;
-  R.key.resize(nit);
-  R.col.resize((size_t)(COARSE_NNZ / 2) * nit);
+  R.meta.assign((size_t)8 * nit, 0u);
   R.val.resize((size_t)COARSE_NNZ * nit);
   R.ainv.resize((size_t)std::max(nsm, 1) * nit);
   for (int t = 0; t < nit; ++t) {
-    R.key[t] = (unsigned)idof[t] | ((unsigned)iloc[t] << 16);
+    // meta: (key, cols 0-2) and (cols 3-4, 0, 0), two 16-byte words per item
+    R.meta[(size_t)t * 4] = (unsigned)idof[t] | ((unsigned)iloc[t] << 16);
     // values in pairs: entries 2e, 2e+1 of item t at [(e * nit + t) * 2 + 0, 1]
     for (int k = 0; k < COARSE_NNZ; ++k)
       R.val[((size_t)(k / 2) * nit + t) * 2 + k % 2] = R.rw_val[(size_t)k * n + idof[t]];
-    for (int k = 0; k < COARSE_NNZ / 2; ++k)
-      R.col[(size_t)k * nit + t] = (unsigned)R.rw_col[(size_t)(2 * k) * n + idof[t]] |
-                                   ((unsigned)R.rw_col[(size_t)(2 * k + 1) * n + idof[t]] << 16);
+    for (int k = 0; k < COARSE_NNZ / 2; ++k) {
+      const unsigned pc = (unsigned)R.rw_col[(size_t)(2 * k) * n + idof[t]] |
+                          ((unsigned)R.rw_col[(size_t)(2 * k + 1) * n + idof[t]] << 16);
+      if (k < 3)
+        R.meta[(size_t)t * 4 + 1 + k] = pc;
+      else
+        R.meta[((size_t)nit + t) * 4 + (k - 3)] = pc;
+    }
     for (int j = 0; j < nsm; ++j) R.ainv[((size_t)(j / 2) * nit + t) * 2 + j % 2] = irow[(size_t)t * nsm + j];
   }
   for (int c = L.ncol - 1; c >= 0; --c)
@@ -1037,14 +1043,12 @@ hdgmg_status build_coarse(hdgmg_ctx* ctx) {
     unsigned* tu;
     TRY(upload(ctx, &ti, R.bwd));
     C.bseq_bwd = ti;
-    TRY(upload(ctx, &tu, R.key));
-    C.it_key = tu;
+    TRY(upload(ctx, &tu, R.meta));
+    C.it_meta = (const uint4*)tu;
     TRY(upload(ctx, &ti, R.cb));
     C.cb_ptr = ti;
     TRY(upload(ctx, &ti, R.bitem));
     C.bitem = ti;
-    TRY(upload(ctx, &tu, R.col));
-    C.it_col = tu;
     TRY(upload_vals(ctx, R.val, &C.it_val));
     TRY(upload_vals(ctx, R.ainv, &C.it_ainv));
     TRY(upload_vals(ctx, R.rw_val, &C.rw_val));
@@ -1080,8 +1084,7 @@ hdgmg_status build_record_levels(hdgmg_ctx* ctx) {
     if (D.fast || 2 * L.nint > 65535 || 2 * L.max_patch_facets > 32) continue;
     LevelRecords R;
     TRY(level_records(ctx, l, GS_REC_THREADS, R));
-    TRY(upload(ctx, &D.rk, R.key));
-    TRY(upload(ctx, &D.rc, R.col));
+    TRY(upload(ctx, &D.rk, R.meta));
     TRY(upload_vals(ctx, R.val, &D.rv));
     TRY(upload_vals(ctx, R.ainv, &D.ra));
     TRY(upload(ctx, &D.rbitem, R.bitem));
