@@ -32,24 +32,31 @@ struct Rec {
   TS ai[NS];
 };
 
-// Pair type of the record values (one 16- or 8-byte load per lane).
+// Groups of record values read with one 16-byte load per lane: pairs of
+// doubles, quads of floats.  get<TS>(v, i) returns component i of a group.
 template <typename TS>
-struct Pair;
+struct Grp;
 template <>
-struct Pair<double> {
+struct Grp<double> {
   using T = double2;
+  static constexpr int G = 2;
+  __device__ static double get(const double2& v, int i) { return i == 0 ? v.x : v.y; }
 };
 template <>
-struct Pair<float> {
-  using T = float2;
+struct Grp<float> {
+  using T = float4;
+  static constexpr int G = 4;
+  __device__ static float get(const float4& v, int i) { return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w; }
 };
 
 template <int NS, typename TS>
 __device__ inline void load_rec(const CoarseLevel& L, int t, Rec<NS, TS>& r) {
-  using P2 = typename Pair<TS>::T;
+  using GT = Grp<TS>;
+  using V = typename GT::T;
+  constexpr int G = GT::G;
   const int nit = L.nitems;
-  const P2* val = (const P2*)L.it_val;
-  const P2* ainv = (const P2*)L.it_ainv;
+  const V* val = (const V*)L.it_val;
+  const V* ainv = (const V*)L.it_ainv;
   const uint4 m0 = L.it_meta[t];
   const uint4 m1 = L.it_meta[nit + t];
   r.key = m0.x;
@@ -58,17 +65,33 @@ __device__ inline void load_rec(const CoarseLevel& L, int t, Rec<NS, TS>& r) {
   r.col[2] = m0.w;
   r.col[3] = m1.x;
   r.col[4] = m1.y;
+  if constexpr (G == 2) {
 #pragma unroll
-  for (int k = 0; k < COARSE_NNZ / 2; ++k) {
-    const P2 v = val[k * nit + t];
-    r.val[2 * k] = v.x;
-    r.val[2 * k + 1] = v.y;
-  }
+    for (int k = 0; k < COARSE_NNZ / 2; ++k) {
+      const V v = val[k * nit + t];
+      r.val[2 * k] = v.x;
+      r.val[2 * k + 1] = v.y;
+    }
 #pragma unroll
-  for (int j = 0; j < NS / 2; ++j) {
-    const P2 v = 2 * j < L.ns_max ? ainv[j * nit + t] : P2{(TS)0, (TS)0};
-    r.ai[2 * j] = v.x;
-    r.ai[2 * j + 1] = v.y;
+    for (int j = 0; j < NS / 2; ++j) {
+      const V v = 2 * j < L.ns_max ? ainv[j * nit + t] : V{(TS)0, (TS)0};
+      r.ai[2 * j] = v.x;
+      r.ai[2 * j + 1] = v.y;
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < (COARSE_NNZ + G - 1) / G; ++e) {
+      const V v = val[e * nit + t];
+#pragma unroll
+      for (int i = 0; i < G; ++i)
+        if (e * G + i < COARSE_NNZ) r.val[e * G + i] = GT::get(v, i);
+    }
+#pragma unroll
+    for (int j = 0; j < NS / G; ++j) {
+      const V v = j * G < L.ns_max ? ainv[j * nit + t] : V{};
+#pragma unroll
+      for (int i = 0; i < G; ++i) r.ai[j * G + i] = GT::get(v, i);
+    }
   }
 }
 
@@ -232,18 +255,26 @@ __global__ void __launch_bounds__(GS_REC_THREADS)
   if (tid < NS) res[GS_REC_THREADS + tid] = 0.0;
   unsigned k = 0;
   double r = 0.0;
-  using P2 = typename Pair<TS>::T;
+  using GT = Grp<TS>;
+  using V = typename GT::T;
+  constexpr int G = GT::G;
   if (on) {
     const uint4 m0 = meta[t], m1 = meta[nit + t];
     const unsigned cols[COARSE_NNZ / 2] = {m0.y, m0.z, m0.w, m1.x, m1.y};
+    TS vals[((COARSE_NNZ + G - 1) / G) * G];
+#pragma unroll
+    for (int e = 0; e < (COARSE_NNZ + G - 1) / G; ++e) {
+      const V v = ((const V*)val)[e * nit + t];
+#pragma unroll
+      for (int i = 0; i < G; ++i) vals[e * G + i] = GT::get(v, i);
+    }
     k = m0.x;
     r = g[k & 0xffff];
 #pragma unroll
     for (int q = 0; q < COARSE_NNZ / 2; ++q) {
       const unsigned c = cols[q];
-      const P2 v = ((const P2*)val)[q * nit + t];
-      r -= (double)v.x * u[c & 0xffff];
-      r -= (double)v.y * u[c >> 16];
+      r -= (double)vals[2 * q] * u[c & 0xffff];
+      r -= (double)vals[2 * q + 1] * u[c >> 16];
     }
   }
   res[tid] = on ? r : 0.0;
@@ -252,9 +283,10 @@ __global__ void __launch_bounds__(GS_REC_THREADS)
     const int base = tid - (int)(k >> 16);
     double d = 0.0;
 #pragma unroll
-    for (int j = 0; j < NS / 2; ++j) {
-      const P2 v = 2 * j < nsm ? ((const P2*)ainv)[j * nit + t] : P2{(TS)0, (TS)0};
-      d += (double)v.x * res[base + 2 * j] + (double)v.y * res[base + 2 * j + 1];
+    for (int j = 0; j < NS / G; ++j) {
+      const V v = j * G < nsm ? ((const V*)ainv)[j * nit + t] : V{};
+#pragma unroll
+      for (int i = 0; i < G; ++i) d += (double)GT::get(v, i) * res[base + j * G + i];
     }
     u[k & 0xffff] += d;
   }

@@ -886,9 +886,9 @@ hdgmg_status build_transfers(hdgmg_ctx* ctx) {
 // row of the patch inverse (host FP64 Cholesky), structure-of-arrays.
 // Patch-row records of a lowest-order level (structure-of-arrays over
 // items; per item two 16-byte meta words (key, columns 0-2), (columns 3-4)
-// at [w][t]; values and
-// inverse rows in pairs, entries 2e and 2e+1 at [(e * nit + t) * 2 + 0, 1] so
-// that a lane reads both with one load): the unknown and its row inside
+// at [w][t]; values and inverse rows in groups of G = 2 (FP64) or 4 (FP32),
+// entry e at [((e / G) * nit + t) * G + e % G], so that a lane reads a group
+// with one 16-byte load): the unknown and its row inside
 // the patch, the padded residual row (16-bit column pairs) and the row of the
 // patch inverse; items colour by colour in patch-aligned batches of at most
 // max_items.  Also the padded residual rows per unknown.
@@ -960,14 +960,17 @@ hdgmg_status level_records(hdgmg_ctx* ctx, int l, int max_items, LevelRecords& R
   const int nit = (int)idof.size();
   R.nit = nit;
   R.meta.assign((size_t)8 * nit, 0u);
-  R.val.resize((size_t)COARSE_NNZ * nit);
-  R.ainv.resize((size_t)std::max(nsm, 1) * nit);
+  // value groups: pairs for FP64 storage, quads for FP32 (16-byte loads)
+  const int G = ctx->opts.vcycle_precision == 1 ? 4 : 2;
+  const int nvg = (COARSE_NNZ + G - 1) / G, nag = (std::max(nsm, 1) + G - 1) / G;
+  R.val.assign((size_t)nvg * G * nit, 0.0);
+  R.ainv.assign((size_t)nag * G * nit, 0.0);
   for (int t = 0; t < nit; ++t) {
     // meta: (key, cols 0-2) and (cols 3-4, 0, 0), two 16-byte words per item
     R.meta[(size_t)t * 4] = (unsigned)idof[t] | ((unsigned)iloc[t] << 16);
-    // values in pairs: entries 2e, 2e+1 of item t at [(e * nit + t) * 2 + 0, 1]
+    // values in groups of G: entry e of item t at [((e / G) * nit + t) * G + e % G]
     for (int k = 0; k < COARSE_NNZ; ++k)
-      R.val[((size_t)(k / 2) * nit + t) * 2 + k % 2] = R.rw_val[(size_t)k * n + idof[t]];
+      R.val[((size_t)(k / G) * nit + t) * G + k % G] = R.rw_val[(size_t)k * n + idof[t]];
     for (int k = 0; k < COARSE_NNZ / 2; ++k) {
       const unsigned pc = (unsigned)R.rw_col[(size_t)(2 * k) * n + idof[t]] |
                           ((unsigned)R.rw_col[(size_t)(2 * k + 1) * n + idof[t]] << 16);
@@ -976,7 +979,7 @@ hdgmg_status level_records(hdgmg_ctx* ctx, int l, int max_items, LevelRecords& R
       else
         R.meta[((size_t)nit + t) * 4 + (k - 3)] = pc;
     }
-    for (int j = 0; j < nsm; ++j) R.ainv[((size_t)(j / 2) * nit + t) * 2 + j % 2] = irow[(size_t)t * nsm + j];
+    for (int j = 0; j < nsm; ++j) R.ainv[((size_t)(j / G) * nit + t) * G + j % G] = irow[(size_t)t * nsm + j];
   }
   for (int c = L.ncol - 1; c >= 0; --c)
     for (int bb = R.cb[c]; bb < R.cb[c + 1]; ++bb) R.bwd.push_back(bb);
