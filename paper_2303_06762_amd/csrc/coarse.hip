@@ -23,6 +23,16 @@ namespace {
 
 constexpr int CT = COARSE_THREADS;
 
+// The descriptors live in LDS, so the compiler cannot tell that the device
+// pointers they hold address global memory and would read through them with
+// flat loads, which are counted together with LDS accesses: every wait for
+// an LDS read would then also wait for all outstanding record loads.  Reads
+// through gmem() are global loads, counted apart.
+template <typename T>
+__device__ inline const __attribute__((address_space(1))) T* gmem(const T* p) {
+  return (const __attribute__((address_space(1))) T*)p;
+}
+
 // The record of one patch row: its unknown and row, residual row, inverse row.
 template <int NS, typename TS>
 struct Rec {
@@ -33,20 +43,22 @@ struct Rec {
 };
 
 // Groups of record values read with one 16-byte load per lane: pairs of
-// doubles, quads of floats.  get<TS>(v, i) returns component i of a group.
+// doubles, quads of floats (native vector types, which load through
+// global-address pointers).  get(v, i) returns component i of a group.
+using u32x4 = unsigned __attribute__((ext_vector_type(4)));
 template <typename TS>
 struct Grp;
 template <>
 struct Grp<double> {
-  using T = double2;
+  using T = double __attribute__((ext_vector_type(2)));
   static constexpr int G = 2;
-  __device__ static double get(const double2& v, int i) { return i == 0 ? v.x : v.y; }
+  __device__ static double get(const T& v, int i) { return v[i]; }
 };
 template <>
 struct Grp<float> {
-  using T = float4;
+  using T = float __attribute__((ext_vector_type(4)));
   static constexpr int G = 4;
-  __device__ static float get(const float4& v, int i) { return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w; }
+  __device__ static float get(const T& v, int i) { return v[i]; }
 };
 
 template <int NS, typename TS>
@@ -55,10 +67,11 @@ __device__ inline void load_rec(const CoarseLevel& L, int t, Rec<NS, TS>& r) {
   using V = typename GT::T;
   constexpr int G = GT::G;
   const int nit = L.nitems;
-  const V* val = (const V*)L.it_val;
-  const V* ainv = (const V*)L.it_ainv;
-  const uint4 m0 = L.it_meta[t];
-  const uint4 m1 = L.it_meta[nit + t];
+  const auto val = gmem((const V*)L.it_val);
+  const auto ainv = gmem((const V*)L.it_ainv);
+  const auto meta = gmem((const u32x4*)L.it_meta);
+  const u32x4 m0 = meta[t];
+  const u32x4 m1 = meta[nit + t];
   r.key = m0.x;
   r.col[0] = m0.y;
   r.col[1] = m0.z;
@@ -74,7 +87,8 @@ __device__ inline void load_rec(const CoarseLevel& L, int t, Rec<NS, TS>& r) {
     }
 #pragma unroll
     for (int j = 0; j < NS / 2; ++j) {
-      const V v = 2 * j < L.ns_max ? ainv[j * nit + t] : V{(TS)0, (TS)0};
+      V v = (V)(TS)0;
+      if (2 * j < L.ns_max) v = ainv[j * nit + t];
       r.ai[2 * j] = v.x;
       r.ai[2 * j + 1] = v.y;
     }
@@ -88,7 +102,8 @@ __device__ inline void load_rec(const CoarseLevel& L, int t, Rec<NS, TS>& r) {
     }
 #pragma unroll
     for (int j = 0; j < NS / G; ++j) {
-      const V v = j * G < L.ns_max ? ainv[j * nit + t] : V{};
+      V v = (V)(TS)0;
+      if (j * G < L.ns_max) v = ainv[j * nit + t];
 #pragma unroll
       for (int i = 0; i < G; ++i) r.ai[j * G + i] = GT::get(v, i);
     }
@@ -96,29 +111,24 @@ __device__ inline void load_rec(const CoarseLevel& L, int t, Rec<NS, TS>& r) {
 }
 
 // `sweeps` block Gauss-Seidel sweeps over the colours (forward or reversed),
-// as a flat list of batches; the next batch's records are loaded while the
-// current batch computes (they do not depend on u).
+// as a flat list of batches.  bitem / bwd: the level's batch item ranges and
+// backward batch order, staged in LDS.  A step loads its records when it
+// starts: the inverse rows arrive while the residual rows are computed.
+// (Holding the next step's records in registers instead, to hide their
+// latency, costs more than it saves: with 1024 threads a lane has 128
+// registers, and the LDS reads of the residual then run one at a time.)
 template <int NS, typename TS>
-__device__ void smooth(const CoarseLevel& L, int sweeps, bool forward, double* __restrict__ res,
-                       double* __restrict__ u, const double* __restrict__ g) {
+__device__ void smooth(const CoarseLevel& L, const int* bitem, const int* bwd, int sweeps, bool forward,
+                       double* __restrict__ res, double* __restrict__ u, const double* __restrict__ g) {
   const int tid = threadIdx.x;
   const int nb = L.nbatch;
   const int steps = sweeps * nb;
-  if (steps == 0) return;
-  auto batch_of = [&](int s) { return forward ? s % nb : L.bseq_bwd[s % nb]; };
-  Rec<NS, TS> cur, nxt;
-  int b = batch_of(0);
-  int t = L.bitem[b] + tid;
-  bool on = t < L.bitem[b + 1];
-  if (on) load_rec<NS, TS>(L, t, cur);
   for (int s = 0; s < steps; ++s) {
-    bool onn = false;
-    if (s + 1 < steps) {
-      const int bn = batch_of(s + 1);
-      const int tn = L.bitem[bn] + tid;
-      onn = tn < L.bitem[bn + 1];
-      if (onn) load_rec<NS, TS>(L, tn, nxt);
-    }
+    const int b = forward ? s % nb : bwd[s % nb];
+    const int t = bitem[b] + tid;
+    const bool on = t < bitem[b + 1];
+    Rec<NS, TS> cur;
+    if (on) load_rec<NS, TS>(L, t, cur);
     const int dof = cur.key & 0xffff, loc = cur.key >> 16;
     if (on) {
       double r = g[dof];
@@ -138,8 +148,6 @@ __device__ void smooth(const CoarseLevel& L, int sweeps, bool forward, double* _
       u[dof] += d;
     }
     __syncthreads();
-    cur = nxt;
-    on = onn;
   }
 }
 
@@ -148,18 +156,25 @@ __global__ void __launch_bounds__(CT) k_coarse_cycle(const CoarseLevel* __restri
                                                      int growth, int q, const TS* __restrict__ inv0, int n0) {
   extern __shared__ double smem[];
   __shared__ CoarseLevel Ls[COARSE_MAX_LEVELS];
+  __shared__ int sbitem[COARSE_MAX_LEVELS][COARSE_MAX_BATCH + 1];
+  __shared__ int sbwd[COARSE_MAX_LEVELS][COARSE_MAX_BATCH];
   const int tid = threadIdx.x;
   double* res = smem;  // [CT + NS], the tail stays zero
   for (int i = tid; i < CT + NS; i += CT) res[i] = 0.0;
   if (tid <= top) Ls[tid] = Lg[tid];
   __syncthreads();
+  for (int l = 1; l <= top; ++l) {
+    const CoarseLevel& L = Ls[l];
+    if (tid <= L.nbatch) sbitem[l][tid] = gmem(L.bitem)[tid];
+    if (tid < L.nbatch) sbwd[l][tid] = gmem(L.bseq_bwd)[tid];
+  }
   {
     const CoarseLevel& T = Ls[top];
     double* u = smem + T.off_u;
     double* g = smem + T.off_g;
     for (int i = tid; i < T.n; i += CT) {
-      u[i] = T.u_glob[i];
-      g[i] = T.g_glob[i];
+      u[i] = gmem(T.u_glob)[i];
+      g[i] = gmem(T.g_glob)[i];
     }
   }
   __syncthreads();
@@ -192,19 +207,22 @@ __global__ void __launch_bounds__(CT) k_coarse_cycle(const CoarseLevel* __restri
     double* ub = smem + B.off_u;
     double* gb = smem + B.off_g;
     if (state[l] == 0) {
-      smooth<NS, TS>(L, mlev[l], true, res, u, g);
-      const TS* rwv = (const TS*)L.rw_val;
-      const TS* Rv = (const TS*)L.R_v;
+      smooth<NS, TS>(L, sbitem[l], sbwd[l], mlev[l], true, res, u, g);
+      const auto rwv = gmem((const TS*)L.rw_val);
+      const auto rwc = gmem(L.rw_col);
+      const auto Rv = gmem((const TS*)L.R_v);
+      const auto Rci = gmem(L.R_ci);
       for (int i = tid; i < L.n; i += CT) {
         double s = g[i];
 #pragma unroll
-        for (int k = 0; k < COARSE_NNZ; ++k) s -= (double)rwv[k * L.n + i] * u[L.rw_col[k * L.n + i]];
+        for (int k = 0; k < COARSE_NNZ; ++k) s -= (double)rwv[k * L.n + i] * u[rwc[k * L.n + i]];
         r[i] = s;
       }
       __syncthreads();
       for (int i = tid; i < B.n; i += CT) {
         double s = 0.0;
-        for (int k = L.R_rp[i]; k < L.R_rp[i + 1]; ++k) s += (double)Rv[k] * r[L.R_ci[k]];
+#pragma unroll 8
+        for (int k = 0; k < L.R_w; ++k) s += (double)Rv[k * B.n + i] * r[Rci[k * B.n + i]];
         gb[i] = s;
         ub[i] = 0.0;
       }
@@ -220,14 +238,16 @@ __global__ void __launch_bounds__(CT) k_coarse_cycle(const CoarseLevel* __restri
       --l;
       continue;
     }
-    const TS* Pv = (const TS*)L.P_v;
+    const auto Pv = gmem((const TS*)L.P_v);
+    const auto Pci = gmem(L.P_ci);
     for (int i = tid; i < L.n; i += CT) {
       double s = 0.0;
-      for (int k = L.P_rp[i]; k < L.P_rp[i + 1]; ++k) s += (double)Pv[k] * ub[L.P_ci[k]];
+#pragma unroll 8
+      for (int k = 0; k < L.P_w; ++k) s += (double)Pv[k * L.n + i] * ub[Pci[k * L.n + i]];
       u[i] += s;
     }
     __syncthreads();
-    smooth<NS, TS>(L, mlev[l], false, res, u, g);
+    smooth<NS, TS>(L, sbitem[l], sbwd[l], mlev[l], false, res, u, g);
     if (l == top) break;
     ++l;
   }
@@ -284,7 +304,7 @@ __global__ void __launch_bounds__(GS_REC_THREADS)
     double d = 0.0;
 #pragma unroll
     for (int j = 0; j < NS / G; ++j) {
-      const V v = j * G < nsm ? ((const V*)ainv)[j * nit + t] : V{};
+      const V v = j * G < nsm ? ((const V*)ainv)[j * nit + t] : (V)(TS)0;
 #pragma unroll
       for (int i = 0; i < G; ++i) d += (double)GT::get(v, i) * res[base + j * G + i];
     }

@@ -36,12 +36,11 @@ struct CoarseLevel {
   const void* it_ainv;        // [ns_max/2][nitems][2] row of the patch inverse (pairs)
   const int* rw_col;          // [COARSE_NNZ][n] rows of A for the residual
   const void* rw_val;
-  const int* R_rp;            // restriction to level l-1 (CSR, its unknowns)
-  const int* R_ci;
-  const void* R_v;
-  const int* P_rp;            // prolongation from level l-1 (CSR, these unknowns)
-  const int* P_ci;
-  const void* P_v;
+  int R_w, P_w;               // ELL widths of the transfers
+  const int* R_ci;            // restriction to level l-1, ELL over its
+  const void* R_v;            // unknowns: slot k of row i at [k * n(l-1) + i]
+  const int* P_ci;            // prolongation from level l-1, ELL over these
+  const void* P_v;            // unknowns: slot k of row i at [k * n + i]
   double* u_glob;             // level vectors in HBM (used at the top level)
   double* g_glob;
 };

@@ -3,8 +3,9 @@
 //
 // Storage (structure-of-arrays so that consecutive threads read consecutive
 // addresses):
-//   Sp   cell blocks of A^eps, packed upper triangle row by row:
-//        entry e of cell K at Sp[e * nc + K]
+//   Sp   cell blocks of A^eps, packed upper triangle row by row, in
+//        16-byte groups (G = 2 doubles or 4 floats): entry e of cell K at
+//        Sp[((e / G) * nc + K) * G + e % G]
 //   cdof per cell and local facet: 2 * interior facet + side (the side the
 //        cell occupies in that facet's cell pair), or -1 on the boundary:
 //        cdof[i * nc + K]
@@ -26,10 +27,30 @@ namespace hdgmg {
 
 namespace {
 
+// Packed blocks are read in 16-byte groups per lane: pairs of doubles,
+// quads of floats (entry e of cell K at [((e / G) * nc + K) * G + e % G]).
+template <typename TS>
+struct Grp;
+template <>
+struct Grp<double> {
+  using T = double2;
+  static constexpr int G = 2;
+  __device__ static double get(const double2& v, int i) { return i == 0 ? v.x : v.y; }
+};
+template <>
+struct Grp<float> {
+  using T = float4;
+  static constexpr int G = 4;
+  __device__ static float get(const float4& v, int i) { return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w; }
+};
+
 template <int M2, typename TS>
 __global__ void __launch_bounds__(256) k_cell_apply(int nc, const TS* __restrict__ Sp, const int* __restrict__ cdof,
                                                     const double* __restrict__ x, double* __restrict__ yF) {
   constexpr int NK = 3 * M2;
+  using GT = Grp<TS>;
+  using V = typename GT::T;
+  constexpr int G = GT::G;
   const int K = blockIdx.x * blockDim.x + threadIdx.x;
   if (K >= nc) return;
   int cd[3];
@@ -42,19 +63,21 @@ __global__ void __launch_bounds__(256) k_cell_apply(int nc, const TS* __restrict
     for (int c = 0; c < M2; ++c) xl[i * M2 + c] = cd[i] >= 0 ? x[(long)(cd[i] >> 1) * M2 + c] : 0.0;
 #pragma unroll
   for (int a = 0; a < NK; ++a) yl[a] = 0.0;
-  // walk the packed entries with a running pointer (stride nc)
-  const TS* q = Sp + K;
+  // walk the packed entries (a, b >= a) in order, one group load per G entries
+  const V* q = (const V*)Sp + K;
+  V cur{};
+  int e = 0;
 #pragma unroll
   for (int a = 0; a < NK; ++a) {
-    double s = (double)*q;
-    q += nc;
-    yl[a] += s * xl[a];
 #pragma unroll
-    for (int b = a + 1; b < NK; ++b) {
-      s = (double)*q;
-      q += nc;
+    for (int b = a; b < NK; ++b, ++e) {
+      if (e % G == 0) {
+        cur = *q;
+        q += nc;
+      }
+      const double s = (double)GT::get(cur, e % G);
       yl[a] += s * xl[b];
-      yl[b] += s * xl[a];
+      if (b != a) yl[b] += s * xl[a];
     }
   }
 #pragma unroll
@@ -130,14 +153,23 @@ __global__ void __launch_bounds__(256) k_patch_relax(int np, const int* __restri
   if (f >= 0) x[(long)f * M2 + i % M2] += d;
 }
 
-// Full row-major cell blocks -> packed SoA.
+// Full row-major cell blocks -> packed SoA in groups of G (G = 2 for the
+// FP64 copy; the FP32 copy is regrouped by k_regroup_f32).
 template <typename TS>
 __global__ void k_pack_cells(int nc, int nK, const double* __restrict__ S, TS* __restrict__ Sp) {
   const int K = blockIdx.x * blockDim.x + threadIdx.x;
   if (K >= nc) return;
   long e = 0;
   for (int a = 0; a < nK; ++a)
-    for (int b = a; b < nK; ++b, ++e) Sp[e * nc + K] = (TS)S[((long)K * nK + a) * nK + b];
+    for (int b = a; b < nK; ++b, ++e) Sp[((e / 2) * nc + K) * 2 + e % 2] = (TS)S[((long)K * nK + a) * nK + b];
+}
+
+// FP64 pair-grouped packed blocks -> FP32 quad-grouped copy.
+__global__ void k_regroup_f32(int nc, long nw, const double* __restrict__ Sp, float* __restrict__ Sp32) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nw * nc) return;
+  const long e = t / nc, K = t % nc;
+  Sp32[((e / 4) * nc + K) * 4 + e % 4] = (float)Sp[((e / 2) * nc + K) * 2 + e % 2];
 }
 
 // Full row-major cell blocks -> [b][K][a] SoA.
@@ -234,6 +266,11 @@ template void launch_patch_relax<double>(hipStream_t, int, int, const int*, cons
                                          const double*, double*);
 template void launch_patch_relax<float>(hipStream_t, int, int, const int*, const float*, const double*,
                                         const double*, double*);
+
+void launch_regroup_cells_f32(hipStream_t st, int nc, int nK, const double* Sp, float* Sp32) {
+  const long nw = (long)nK * (nK + 1) / 2;
+  if (nc > 0) hipLaunchKernelGGL(k_regroup_f32, dim3(nblk(nw * nc)), dim3(256), 0, st, nc, nw, Sp, Sp32);
+}
 
 void launch_pack_cells(hipStream_t st, int nc, int nK, const double* S, double* Sp, bool full) {
   if (nc <= 0) return;

@@ -14,8 +14,10 @@ constexpr int FAST_NF = 6;
 // symmetric blocks up to 18 x 18 (k <= 2), full otherwise (full = true for
 // the nonsymmetric blocks of the Oseen operator).
 inline bool fast_cell_packed(int nK, bool full) { return nK <= 18 && !full; }
+// Packed blocks are stored in 16-byte groups (pairs of doubles, quads of
+// floats): room for the words rounded up to a multiple of 4.
 inline long fast_cell_words(int nK, bool full = false) {
-  return fast_cell_packed(nK, full) ? (long)nK * (nK + 1) / 2 : (long)nK * nK;
+  return fast_cell_packed(nK, full) ? ((long)nK * (nK + 1) / 2 + 3) / 4 * 4 : (long)nK * nK;
 }
 
 // y_F[(2F+side)*m2 + c] = rows of S_K x_K for every cell K (m2 = 2 modes
@@ -31,6 +33,8 @@ template <typename TS>
 void launch_patch_relax(hipStream_t st, int m2, int np, const int* pf, const TS* Pp, const double* b,
                         const double* yF, double* x);
 void launch_pack_cells(hipStream_t st, int nc, int nK, const double* S, double* Sp, bool full = false);
+// FP32 copy of packed blocks (pair groups -> quad groups).
+void launch_regroup_cells_f32(hipStream_t st, int nc, int nK, const double* Sp, float* Sp32);
 void launch_pack_patches(hipStream_t st, int np, int gp0, int m2, const int* pf_ptr, const long* pinv_off,
                          const double* pinv, double* Pp);
 

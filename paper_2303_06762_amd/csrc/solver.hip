@@ -116,18 +116,15 @@ struct DevLevel {
   }
 };
 
+// Prolongation and restriction of a level in ELL form (column-major, zero
+// padded); nnz: stored entries of the larger of the two.
 struct DevTransfer {
   int nfine = 0, ncoarse = 0;
   long nnz = 0;
-  int *P_rp = nullptr, *P_ci = nullptr;
-  double* P_v = nullptr;
-  int *R_rp = nullptr, *R_ci = nullptr;
-  double* R_v = nullptr;
-  // the same operators in ELL form for the per-level launches
   int Pw = 0, Rw = 0;
   int *Pe_ci = nullptr, *Re_ci = nullptr;
   double *Pe_v = nullptr, *Re_v = nullptr;
-  float *Pe_v32 = nullptr, *Re_v32 = nullptr, *P_v32 = nullptr, *R_v32 = nullptr;
+  float *Pe_v32 = nullptr, *Re_v32 = nullptr;
 };
 
 // CSR -> ELL (column-major, zero padding).
@@ -451,7 +448,10 @@ hdgmg_status make_f32(hdgmg_ctx* ctx, DevLevel& D) {
   if (D.fast) {
     long nSp = (long)D.nc * D.sp_words;
     TRY(dalloc(ctx, &D.Sp32, (size_t)nSp));
-    launch_to_f32(ctx->st, nSp, D.Sp, D.Sp32);
+    if (fast_cell_packed(D.nK, D.full))
+      launch_regroup_cells_f32(ctx->st, D.nc, D.nK, D.Sp, D.Sp32);
+    else
+      launch_to_f32(ctx->st, nSp, D.Sp, D.Sp32);
     const long NS = (long)FAST_NF * 2 * D.m;
     D.Pp32.assign(D.Ppc.size(), nullptr);
     for (size_t c = 0; c < D.Ppc.size(); ++c) {
@@ -849,22 +849,12 @@ hdgmg_status build_transfers(hdgmg_ctx* ctx) {
     Tt.nfine = P.n;
     Tt.ncoarse = R.n;
     Tt.nnz = (long)std::max(P.ci.size(), R.ci.size());
-    TRY(upload(ctx, &Tt.P_rp, P.rp));
-    TRY(upload(ctx, &Tt.P_ci, P.ci));
-    TRY(upload(ctx, &Tt.P_v, P.v));
-    TRY(upload(ctx, &Tt.R_rp, R.rp));
-    TRY(upload(ctx, &Tt.R_ci, R.ci));
-    TRY(upload(ctx, &Tt.R_v, R.v));
     std::vector<int> eci;
     std::vector<double> ev;
     to_ell(P, Tt.Pw, eci, ev);
     TRY(upload(ctx, &Tt.Pe_ci, eci));
     TRY(upload(ctx, &Tt.Pe_v, ev));
-    if (ctx->opts.vcycle_precision == 1) {
-      TRY(upload_f32(ctx, &Tt.Pe_v32, ev));
-      TRY(upload_f32(ctx, &Tt.P_v32, P.v));
-      TRY(upload_f32(ctx, &Tt.R_v32, R.v));
-    }
+    if (ctx->opts.vcycle_precision == 1) TRY(upload_f32(ctx, &Tt.Pe_v32, ev));
     to_ell(R, Tt.Rw, eci, ev);
     TRY(upload(ctx, &Tt.Re_ci, eci));
     TRY(upload(ctx, &Tt.Re_v, ev));
@@ -1059,12 +1049,12 @@ hdgmg_status build_coarse(hdgmg_ctx* ctx) {
     C.rw_col = ti;
     const bool f32 = ctx->opts.vcycle_precision == 1;
     const DevTransfer& T = ctx->tr[l];
-    C.R_rp = T.R_rp;
-    C.R_ci = T.R_ci;
-    C.R_v = f32 ? (const void*)T.R_v32 : (const void*)T.R_v;
-    C.P_rp = T.P_rp;
-    C.P_ci = T.P_ci;
-    C.P_v = f32 ? (const void*)T.P_v32 : (const void*)T.P_v;
+    C.R_w = T.Rw;
+    C.R_ci = T.Re_ci;
+    C.R_v = f32 ? (const void*)T.Re_v32 : (const void*)T.Re_v;
+    C.P_w = T.Pw;
+    C.P_ci = T.Pe_ci;
+    C.P_v = f32 ? (const void*)T.Pe_v32 : (const void*)T.Pe_v;
   }
   std::vector<char> raw(sizeof(CoarseLevel) * desc.size());
   std::memcpy(raw.data(), desc.data(), raw.size());
