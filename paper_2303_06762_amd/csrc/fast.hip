@@ -14,12 +14,19 @@
 //   pf   per patch of one colour its facets, padded with -1: pf[a * np + p]
 //   Sf   (k >= 3) cell blocks in full: entry (a, b) of cell K at
 //        Sf[(b * nc + K) * NK + a]; a thread per (cell, row)
-//   Pp   patch inverses in full, zero-padded to FAST_NF facets: entry (i, j)
-//        of patch p at Pp[(j * np + p) * NS + i]; a thread per (patch, row)
-//        so that every j-step reads one contiguous run of the workgroup
+//   Pp   patch inverses, zero-padded to FAST_NF facets (NS = FAST_NF m2 rows).
+//        Nonsymmetric operators: in full, entry (i, j) of patch p at
+//        Pp[(j * np + p) * NS + i]; a thread per (patch, row) so that every
+//        j-step reads one contiguous run of the workgroup.  Symmetric
+//        operators: the upper triangle, entry (a <= b) at Pp[e(a, b) * np + p]
+//        with e(a, b) = a NS - a (a - 1) / 2 + b - a; a thread per (row,
+//        patch), 16 consecutive patches per row, so that a wavefront reads
+//        four 16-patch runs per step
 // A Gauss-Seidel colour phase is a cell apply (y = S x for every cell) then
 // k_patch_relax (x_s += A_ss^-1 (b - y)_s for the colour's patches).
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "fast.hpp"
 
@@ -153,6 +160,49 @@ __global__ void __launch_bounds__(256) k_patch_relax(int np, const int* __restri
   if (f >= 0) x[(long)f * M2 + i % M2] += d;
 }
 
+// The same relaxation from the upper triangle of symmetric FP64 inverses.
+// Row i of an inverse is row i of the upper triangle joined with column i:
+// at step t the thread of row i takes column j = (t - i) mod NS, so that
+// entry (min(i, j), max(i, j)) is read for rows i and j of the same patch
+// in the same step and the second read is served by the cache.  A row group
+// is 16 consecutive patches (128 bytes per entry).  Residuals are held in LDS
+// as rs[j][patch] so that a row group reads consecutive words.  The offsets
+// of step t for row i, (e np, j 16), are tabulated in LDS once per
+// workgroup; they are 32-bit: the host keeps np * NS (NS + 1) / 2 below 2^31.
+constexpr int SYM_PB = 16;
+template <int M2>
+__global__ void __launch_bounds__(FAST_NF * M2 * SYM_PB)
+    k_patch_relax_sym(int np, const int* __restrict__ pf, const double* __restrict__ Pp,
+                      const double* __restrict__ b, const double* __restrict__ yF, double* __restrict__ x) {
+  constexpr int NS = FAST_NF * M2, PB = SYM_PB;
+  __shared__ double rs[NS * PB];
+  __shared__ uint2 tab[NS * NS];
+  for (int k = threadIdx.x; k < NS * NS; k += NS * PB) {
+    const int t = k / NS, i = k % NS;
+    int j = t - i;
+    if (j < 0) j += NS;
+    const int a = min(i, j), e = a * NS - a * (a - 1) / 2 + max(i, j) - a;
+    tab[k] = make_uint2((unsigned)e * (unsigned)np, (unsigned)(j * PB));
+  }
+  const int i = threadIdx.x / PB, lp = threadIdx.x % PB, c = i % M2;
+  const int p = blockIdx.x * PB + lp;
+  const bool on = p < np;
+  const int f = on ? pf[(i / M2) * np + p] : -1;
+  rs[i * PB + lp] =
+      f >= 0 ? b[(long)f * M2 + c] - yF[(long)(2 * f) * M2 + c] - yF[(long)(2 * f + 1) * M2 + c] : 0.0;
+  __syncthreads();
+  if (!on) return;
+  const double* Pq = Pp + p;
+  const double* rq = rs + lp;
+  double d = 0.0;
+#pragma unroll
+  for (int t = 0; t < NS; ++t) {
+    const uint2 o = tab[t * NS + i];
+    d += Pq[o.x] * rq[o.y];
+  }
+  if (f >= 0) x[(long)f * M2 + c] += d;
+}
+
 // Full row-major cell blocks -> packed SoA in groups of G (G = 2 for the
 // FP64 copy; the FP32 copy is regrouped by k_regroup_f32).
 template <typename TS>
@@ -198,6 +248,24 @@ __global__ void k_pack_patches(int np, int gp0, int m2, const int* __restrict__ 
       Pp[((long)j * np + p) * NS + i] = (i < ns && j < ns) ? (TS)A[(long)j * ns + i] : (TS)0;
 }
 
+// Column-major per-patch inverses -> symmetric upper-triangle layout (the
+// mean of the two computed entries).
+template <typename TS>
+__global__ void k_pack_patches_sym(int np, int gp0, int m2, const int* __restrict__ pf_ptr,
+                                   const long* __restrict__ pinv_off, const double* __restrict__ pinv,
+                                   TS* __restrict__ Pp) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  const int gp = gp0 + p;
+  const int ns = (pf_ptr[gp + 1] - pf_ptr[gp]) * m2;
+  const int NS = FAST_NF * m2;
+  const double* A = pinv + pinv_off[gp];
+  long e = 0;
+  for (int a = 0; a < NS; ++a)
+    for (int c = a; c < NS; ++c, ++e)
+      Pp[e * np + p] = (a < ns && c < ns) ? (TS)(0.5 * (A[(long)c * ns + a] + A[(long)a * ns + c])) : (TS)0;
+}
+
 inline int nblk(long n, int t = 256) { return (int)((n + t - 1) / t); }
 
 template <typename TS>
@@ -227,7 +295,21 @@ void cell_apply_t(hipStream_t st, int m2, int nc, const TS* Sp, const int* cdof,
 
 template <typename TS>
 void patch_relax_t(hipStream_t st, int m2, int np, const int* pf, const TS* Pp, const double* b, const double* yF,
-                   double* x) {
+                   double* x, bool full) {
+  if constexpr (std::is_same<TS, double>::value) {
+    if (!full) {
+      switch (m2) {
+#define CASE(M)                                                                                            \
+  case M:                                                                                                  \
+    hipLaunchKernelGGL((k_patch_relax_sym<M>), dim3((np + SYM_PB - 1) / SYM_PB), dim3(FAST_NF * M * SYM_PB), 0, st, \
+                       np, pf, Pp, b, yF, x);                                                              \
+    break;
+        CASE(2) CASE(4) CASE(6) CASE(8) CASE(10)
+#undef CASE
+      }
+      return;
+    }
+  }
   switch (m2) {
 #define CASE(M)                                                                                            \
   case M:                                                                                                  \
@@ -259,13 +341,13 @@ void launch_facet_sum(hipStream_t st, int nint, int m2, const double* yF, const 
 
 template <typename TS>
 void launch_patch_relax(hipStream_t st, int m2, int np, const int* pf, const TS* Pp, const double* b,
-                        const double* yF, double* x) {
-  if (np > 0) patch_relax_t<TS>(st, m2, np, pf, Pp, b, yF, x);
+                        const double* yF, double* x, bool full) {
+  if (np > 0) patch_relax_t<TS>(st, m2, np, pf, Pp, b, yF, x, full);
 }
 template void launch_patch_relax<double>(hipStream_t, int, int, const int*, const double*, const double*,
-                                         const double*, double*);
+                                         const double*, double*, bool);
 template void launch_patch_relax<float>(hipStream_t, int, int, const int*, const float*, const double*,
-                                        const double*, double*);
+                                        const double*, double*, bool);
 
 void launch_regroup_cells_f32(hipStream_t st, int nc, int nK, const double* Sp, float* Sp32) {
   const long nw = (long)nK * (nK + 1) / 2;
@@ -281,10 +363,14 @@ void launch_pack_cells(hipStream_t st, int nc, int nK, const double* S, double* 
 }
 
 void launch_pack_patches(hipStream_t st, int np, int gp0, int m2, const int* pf_ptr, const long* pinv_off,
-                         const double* pinv, double* Pp) {
-  if (np > 0)
+                         const double* pinv, double* Pp, bool full) {
+  if (np <= 0) return;
+  if (full)
     hipLaunchKernelGGL(k_pack_patches<double>, dim3(nblk(np)), dim3(256), 0, st, np, gp0, m2, pf_ptr, pinv_off,
                        pinv, Pp);
+  else
+    hipLaunchKernelGGL(k_pack_patches_sym<double>, dim3(nblk(np)), dim3(256), 0, st, np, gp0, m2, pf_ptr,
+                       pinv_off, pinv, Pp);
 }
 
 }  // namespace hdgmg

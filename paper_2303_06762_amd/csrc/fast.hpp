@@ -20,6 +20,14 @@ inline long fast_cell_words(int nK, bool full = false) {
   return fast_cell_packed(nK, full) ? ((long)nK * (nK + 1) / 2 + 3) / 4 * 4 : (long)nK * nK;
 }
 
+// Patch-inverse storage: the upper triangle of each zero-padded FAST_NF*m2
+// square inverse (full = false: symmetric operators, FP64 only), else the
+// square.
+inline long fast_patch_words(int m2, bool full) {
+  const long ns = (long)FAST_NF * m2;
+  return full ? ns * ns : ns * (ns + 1) / 2;
+}
+
 // y_F[(2F+side)*m2 + c] = rows of S_K x_K for every cell K (m2 = 2 modes
 // per facet component x 2 components).
 template <typename TS>
@@ -28,14 +36,16 @@ void launch_cell_apply(hipStream_t st, int m2, int nc, const TS* Sp, const int* 
 // y = b + alpha * (y_F[side 0] + y_F[side 1]) (b may be null)
 void launch_facet_sum(hipStream_t st, int nint, int m2, const double* yF, const double* b, double alpha,
                       double* y);
-// x_s += A_ss^-1 (b - y)_s for the np patches of one colour
+// x_s += A_ss^-1 (b - y)_s for the np patches of one colour (Pp in the
+// layout fast_patch_words(m2, full) describes; full = false only for TS =
+// double)
 template <typename TS>
 void launch_patch_relax(hipStream_t st, int m2, int np, const int* pf, const TS* Pp, const double* b,
-                        const double* yF, double* x);
+                        const double* yF, double* x, bool full = true);
 void launch_pack_cells(hipStream_t st, int nc, int nK, const double* S, double* Sp, bool full = false);
 // FP32 copy of packed blocks (pair groups -> quad groups).
 void launch_regroup_cells_f32(hipStream_t st, int nc, int nK, const double* Sp, float* Sp32);
 void launch_pack_patches(hipStream_t st, int np, int gp0, int m2, const int* pf_ptr, const long* pinv_off,
-                         const double* pinv, double* Pp);
+                         const double* pinv, double* Pp, bool full = true);
 
 }  // namespace hdgmg

@@ -73,6 +73,7 @@ struct DevLevel {
   std::vector<int> npc;   // patches per colour
   std::vector<int*> pfc;  // per colour [FAST_NF][npc] facets
   std::vector<double*> Ppc;  // per colour packed SoA patch inverses
+  bool pfull = true;         // patch inverses stored in full (else upper triangles)
   double bytes_cell = 0.0, bytes_sum = 0.0;
   std::vector<double> bytes_relax;
   // storage the preconditioner reads: FP64 arrays above, or FP32 copies
@@ -375,7 +376,14 @@ hdgmg_status upload_level(hdgmg_ctx* ctx, const Level& L, int m, DevLevel& D) {
     const double ws = ctx->opts.vcycle_precision == 1 ? 4.0 : 8.0;
     D.bytes_cell_vc = (double)L.nc * D.sp_words * ws + vec;
     D.bytes_sum = 3.0 * L.nint * m2 * 8.0;
-    const int NS = FAST_NF * m2;
+    // symmetric FP64 patch inverses are stored as upper triangles, addressed
+    // with 32-bit offsets (the FP32 copies of the mixed V-cycle stay square:
+    // their streaming relaxation is faster than the triangular one)
+    int np_max = 0;
+    for (int cc = 0; cc < L.ncol; ++cc) np_max = std::max(np_max, L.colour_ptr[cc + 1] - L.colour_ptr[cc]);
+    D.pfull = D.full || ctx->opts.vcycle_precision == 1 ||
+              (long)np_max * fast_patch_words(m2, false) >= (1L << 31);
+    const long pw = fast_patch_words(m2, D.pfull);
     for (int cc = 0; cc < L.ncol; ++cc) {
       int p0 = L.colour_ptr[cc], np = L.colour_ptr[cc + 1] - p0;
       std::vector<int> pf((size_t)FAST_NF * std::max(np, 1), -1);
@@ -388,12 +396,12 @@ hdgmg_status upload_level(hdgmg_ctx* ctx, const Level& L, int m, DevLevel& D) {
       int* dpf;
       double* dPp;
       TRY(upload(ctx, &dpf, pf));
-      TRY(dalloc(ctx, &dPp, (size_t)std::max(np, 1) * NS * NS));
+      TRY(dalloc(ctx, &dPp, (size_t)std::max(np, 1) * pw));
       D.npc.push_back(np);
       D.pfc.push_back(dpf);
       D.Ppc.push_back(dPp);
-      D.bytes_relax.push_back((double)np * NS * NS * 8.0 + np * FAST_NF * 4.0 + 5.0 * nfac * m2 * 8.0);
-      D.bytes_relax_vc.push_back((double)np * NS * NS * ws + np * FAST_NF * 4.0 + 5.0 * nfac * m2 * 8.0);
+      D.bytes_relax.push_back((double)np * pw * 8.0 + np * FAST_NF * 4.0 + 5.0 * nfac * m2 * 8.0);
+      D.bytes_relax_vc.push_back((double)np * pw * ws + np * FAST_NF * 4.0 + 5.0 * nfac * m2 * 8.0);
     }
   }
   TRY(dalloc(ctx, &D.u, (size_t)D.ndof));
@@ -431,7 +439,8 @@ hdgmg_status pack_fast(hdgmg_ctx* ctx, DevLevel& D) {
   if (!D.fast) return HDGMG_OK;
   launch_pack_cells(ctx->st, D.nc, D.nK, D.S, D.Sp, D.full);
   for (size_t c = 0; c < D.npc.size(); ++c)
-    launch_pack_patches(ctx->st, D.npc[c], D.colour_ptr[c], 2 * D.m, D.pf_ptr, D.pinv_off, D.pinv, D.Ppc[c]);
+    launch_pack_patches(ctx->st, D.npc[c], D.colour_ptr[c], 2 * D.m, D.pf_ptr, D.pinv_off, D.pinv, D.Ppc[c],
+                        D.pfull);
   HIPC(hipGetLastError());
   return HDGMG_OK;
 }
@@ -452,10 +461,10 @@ hdgmg_status make_f32(hdgmg_ctx* ctx, DevLevel& D) {
       launch_regroup_cells_f32(ctx->st, D.nc, D.nK, D.Sp, D.Sp32);
     else
       launch_to_f32(ctx->st, nSp, D.Sp, D.Sp32);
-    const long NS = (long)FAST_NF * 2 * D.m;
+    const long pw = fast_patch_words(2 * D.m, D.pfull);
     D.Pp32.assign(D.Ppc.size(), nullptr);
     for (size_t c = 0; c < D.Ppc.size(); ++c) {
-      long n = std::max(D.npc[c], 1) * NS * NS;
+      long n = std::max(D.npc[c], 1) * pw;
       TRY(dalloc(ctx, &D.Pp32[c], (size_t)n));
       launch_to_f32(ctx->st, n, D.Ppc[c], D.Pp32[c]);
     }
@@ -494,9 +503,9 @@ void sweep(hdgmg_ctx* ctx, DevLevel& D, double* x, const double* b, bool forward
       kt_end(ctx, level < 0 ? 1 : 2, t, D.bytes_cell_vc);
       t = kt_begin(ctx, level < 0 ? 0 : 2);
       if (D.f32)
-        launch_patch_relax<float>(ctx->st, 2 * D.m, D.npc[c], D.pfc[c], D.Pp32[c], b, D.yF, x);
+        launch_patch_relax<float>(ctx->st, 2 * D.m, D.npc[c], D.pfc[c], D.Pp32[c], b, D.yF, x, D.pfull);
       else
-        launch_patch_relax<double>(ctx->st, 2 * D.m, D.npc[c], D.pfc[c], D.Ppc[c], b, D.yF, x);
+        launch_patch_relax<double>(ctx->st, 2 * D.m, D.npc[c], D.pfc[c], D.Ppc[c], b, D.yF, x, D.pfull);
       kt_end(ctx, level < 0 ? 0 : 2, t, D.bytes_relax_vc[c]);
     } else if (D.rec) {
       int t = kt_begin(ctx, 2);
