@@ -61,52 +61,84 @@ struct Grp<float> {
   __device__ static float get(const T& v, int i) { return v[i]; }
 };
 
+// Record parts come from LDS (copied at kernel start) or from memory; each
+// part's source is uniform per level.  Part pointers are typed per address
+// space so that LDS parts are read with LDS instructions.
 template <int NS, typename TS>
-__device__ inline void load_rec(const CoarseLevel& L, int t, Rec<NS, TS>& r) {
+__device__ inline void load_rec(const CoarseLevel& L, const char* lds, int t, Rec<NS, TS>& r) {
   using GT = Grp<TS>;
   using V = typename GT::T;
   constexpr int G = GT::G;
   const int nit = L.nitems;
-  const auto val = gmem((const V*)L.it_val);
-  const auto ainv = gmem((const V*)L.it_ainv);
-  const auto meta = gmem((const u32x4*)L.it_meta);
-  const u32x4 m0 = meta[t];
-  const u32x4 m1 = meta[nit + t];
+  u32x4 m0, m1;
+  if (L.lds_meta >= 0) {
+    const u32x4* meta = (const u32x4*)(lds + L.lds_meta);
+    m0 = meta[t];
+    m1 = meta[nit + t];
+  } else {
+    const auto meta = gmem((const u32x4*)L.it_meta);
+    m0 = meta[t];
+    m1 = meta[nit + t];
+  }
   r.key = m0.x;
   r.col[0] = m0.y;
   r.col[1] = m0.z;
   r.col[2] = m0.w;
   r.col[3] = m1.x;
   r.col[4] = m1.y;
-  if constexpr (G == 2) {
+  constexpr int NVG = (COARSE_NNZ + G - 1) / G;
+  V vg[NVG];
+  if (L.lds_val >= 0) {
+    const V* val = (const V*)(lds + L.lds_val);
 #pragma unroll
-    for (int k = 0; k < COARSE_NNZ / 2; ++k) {
-      const V v = val[k * nit + t];
-      r.val[2 * k] = v.x;
-      r.val[2 * k + 1] = v.y;
-    }
-#pragma unroll
-    for (int j = 0; j < NS / 2; ++j) {
-      V v = (V)(TS)0;
-      if (2 * j < L.ns_max) v = ainv[j * nit + t];
-      r.ai[2 * j] = v.x;
-      r.ai[2 * j + 1] = v.y;
-    }
+    for (int e = 0; e < NVG; ++e) vg[e] = val[e * nit + t];
   } else {
+    const auto val = gmem((const V*)L.it_val);
 #pragma unroll
-    for (int e = 0; e < (COARSE_NNZ + G - 1) / G; ++e) {
-      const V v = val[e * nit + t];
+    for (int e = 0; e < NVG; ++e) vg[e] = val[e * nit + t];
+  }
 #pragma unroll
-      for (int i = 0; i < G; ++i)
-        if (e * G + i < COARSE_NNZ) r.val[e * G + i] = GT::get(v, i);
-    }
+  for (int e = 0; e < NVG; ++e)
+#pragma unroll
+    for (int i = 0; i < G; ++i)
+      if (e * G + i < COARSE_NNZ) r.val[e * G + i] = GT::get(vg[e], i);
+  V ag[NS / G];
+  if (L.lds_ainv >= 0) {
+    const V* ainv = (const V*)(lds + L.lds_ainv);
 #pragma unroll
     for (int j = 0; j < NS / G; ++j) {
-      V v = (V)(TS)0;
-      if (j * G < L.ns_max) v = ainv[j * nit + t];
-#pragma unroll
-      for (int i = 0; i < G; ++i) r.ai[j * G + i] = GT::get(v, i);
+      ag[j] = (V)(TS)0;
+      if (j * G < L.ns_max) ag[j] = ainv[j * nit + t];
     }
+  } else {
+    const auto ainv = gmem((const V*)L.it_ainv);
+#pragma unroll
+    for (int j = 0; j < NS / G; ++j) {
+      ag[j] = (V)(TS)0;
+      if (j * G < L.ns_max) ag[j] = ainv[j * nit + t];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NS / G; ++j)
+#pragma unroll
+    for (int i = 0; i < G; ++i) r.ai[j * G + i] = GT::get(ag[j], i);
+}
+
+// Copy n 16-byte words from memory to LDS with the whole workgroup, eight
+// loads in flight per thread before the stores.
+__device__ inline void copy_to_lds(void* dst, const void* src, int n) {
+  u32x4* d = (u32x4*)dst;
+  const auto sp = gmem((const u32x4*)src);
+  for (int i0 = threadIdx.x; i0 < n; i0 += 8 * CT) {
+    u32x4 w[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int i = min(i0 + q * CT, n - 1);
+      w[q] = sp[i];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (i0 + q * CT < n) d[i0 + q * CT] = w[q];
   }
 }
 
@@ -118,8 +150,12 @@ __device__ inline void load_rec(const CoarseLevel& L, int t, Rec<NS, TS>& r) {
 // latency, costs more than it saves: with 1024 threads a lane has 128
 // registers, and the LDS reads of the residual then run one at a time.)
 template <int NS, typename TS>
-__device__ void smooth(const CoarseLevel& L, const int* bitem, const int* bwd, int sweeps, bool forward,
-                       double* __restrict__ res, double* __restrict__ u, const double* __restrict__ g) {
+__device__ void smooth(const CoarseLevel& Ld, const char* lds, const int* bitem, const int* bwd, int sweeps,
+                       bool forward, double* __restrict__ res, double* __restrict__ u,
+                       const double* __restrict__ g) {
+  // the descriptor is read from LDS once: inside the loop its fields would
+  // be re-read after every barrier
+  const CoarseLevel L = Ld;
   const int tid = threadIdx.x;
   const int nb = L.nbatch;
   const int steps = sweeps * nb;
@@ -128,7 +164,7 @@ __device__ void smooth(const CoarseLevel& L, const int* bitem, const int* bwd, i
     const int t = bitem[b] + tid;
     const bool on = t < bitem[b + 1];
     Rec<NS, TS> cur;
-    if (on) load_rec<NS, TS>(L, t, cur);
+    if (on) load_rec<NS, TS>(L, lds, t, cur);
     const int dof = cur.key & 0xffff, loc = cur.key >> 16;
     if (on) {
       double r = g[dof];
@@ -163,10 +199,17 @@ __global__ void __launch_bounds__(CT) k_coarse_cycle(const CoarseLevel* __restri
   for (int i = tid; i < CT + NS; i += CT) res[i] = 0.0;
   if (tid <= top) Ls[tid] = Lg[tid];
   __syncthreads();
+  const char* lds = (const char*)smem;
+  constexpr int G = Grp<TS>::G;
   for (int l = 1; l <= top; ++l) {
     const CoarseLevel& L = Ls[l];
     if (tid <= L.nbatch) sbitem[l][tid] = gmem(L.bitem)[tid];
     if (tid < L.nbatch) sbwd[l][tid] = gmem(L.bseq_bwd)[tid];
+    // record parts resident in LDS for the whole kernel (16-byte words)
+    const int nit = L.nitems;
+    if (L.lds_meta >= 0) copy_to_lds((char*)smem + L.lds_meta, L.it_meta, 2 * nit);
+    if (L.lds_val >= 0) copy_to_lds((char*)smem + L.lds_val, L.it_val, (COARSE_NNZ + G - 1) / G * nit);
+    if (L.lds_ainv >= 0) copy_to_lds((char*)smem + L.lds_ainv, L.it_ainv, (L.ns_max + G - 1) / G * nit);
   }
   {
     const CoarseLevel& T = Ls[top];
@@ -207,7 +250,7 @@ __global__ void __launch_bounds__(CT) k_coarse_cycle(const CoarseLevel* __restri
     double* ub = smem + B.off_u;
     double* gb = smem + B.off_g;
     if (state[l] == 0) {
-      smooth<NS, TS>(L, sbitem[l], sbwd[l], mlev[l], true, res, u, g);
+      smooth<NS, TS>(L, lds, sbitem[l], sbwd[l], mlev[l], true, res, u, g);
       const auto rwv = gmem((const TS*)L.rw_val);
       const auto rwc = gmem(L.rw_col);
       const auto Rv = gmem((const TS*)L.R_v);
@@ -247,7 +290,7 @@ __global__ void __launch_bounds__(CT) k_coarse_cycle(const CoarseLevel* __restri
       u[i] += s;
     }
     __syncthreads();
-    smooth<NS, TS>(L, sbitem[l], sbwd[l], mlev[l], false, res, u, g);
+    smooth<NS, TS>(L, lds, sbitem[l], sbwd[l], mlev[l], false, res, u, g);
     if (l == top) break;
     ++l;
   }
@@ -347,6 +390,24 @@ void coarse_t(hipStream_t st, const CoarseLevel* Ls, int top, int m_top, int gro
     hipLaunchKernelGGL((k_coarse_cycle<16, TS>), dim3(1), dim3(CT), shm, st, Ls, top, m_top, growth, q, inv0, n0);
   else
     hipLaunchKernelGGL((k_coarse_cycle<32, TS>), dim3(1), dim3(CT), shm, st, Ls, top, m_top, growth, q, inv0, n0);
+}
+
+template <typename TS>
+hipError_t prepare_t(int ns_max, size_t lds_bytes) {
+  const int v = (int)lds_bytes;
+  if (ns_max <= 12)
+    return hipFuncSetAttribute((const void*)k_coarse_cycle<12, TS>, hipFuncAttributeMaxDynamicSharedMemorySize, v);
+  if (ns_max <= 16)
+    return hipFuncSetAttribute((const void*)k_coarse_cycle<16, TS>, hipFuncAttributeMaxDynamicSharedMemorySize, v);
+  return hipFuncSetAttribute((const void*)k_coarse_cycle<32, TS>, hipFuncAttributeMaxDynamicSharedMemorySize, v);
+}
+
+hipError_t prepare_coarse_cycle(int ns_max, size_t lds_bytes, int f32) {
+  return f32 ? prepare_t<float>(ns_max, lds_bytes) : prepare_t<double>(ns_max, lds_bytes);
+}
+
+size_t coarse_cycle_static_lds() {
+  return sizeof(CoarseLevel) * COARSE_MAX_LEVELS + sizeof(int) * COARSE_MAX_LEVELS * (2 * COARSE_MAX_BATCH + 1);
 }
 
 void launch_coarse_cycle(hipStream_t st, const CoarseLevel* Ls, int top, int m_top, int growth, int q,

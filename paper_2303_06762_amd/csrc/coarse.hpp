@@ -14,6 +14,8 @@ constexpr int COARSE_NNZ = 10;
 constexpr int COARSE_LDS_DOUBLES = 6144;
 // Largest number of batches of one level's sweep (its schedule is staged in LDS).
 constexpr int COARSE_MAX_BATCH = 64;
+// LDS of one workgroup on gfx950.
+constexpr int COARSE_LDS_BYTES = 160 * 1024;
 
 // One lowest-order level as seen by the coarse kernel (device pointers;
 // per-item arrays are structure-of-arrays: entry e of item t at [e*nitems+t]).
@@ -24,6 +26,8 @@ struct CoarseLevel {
   int ncol, nitems, ns_max;   // colours, patch rows, largest patch
   int nbatch;
   int off_u, off_g, off_r;    // LDS offsets of the level vectors (doubles)
+  int lds_meta, lds_val, lds_ainv;  // byte offsets of record parts copied
+                              // to LDS at kernel start, -1: read from memory
   const int* cb_ptr;          // [ncol+1] batch range of each colour
   const int* bitem;           // [nbatch+1] item range of each batch
                               // (<= COARSE_THREADS items, patch-aligned)
@@ -61,6 +65,11 @@ void launch_gs_records(hipStream_t st, const unsigned* meta, const void* val, co
 // the dense column-major inverse inv0 (n0 x n0).  lds_doubles: the dynamic
 // LDS the descriptors' offsets need.
 // f32 != 0: operator values (and inv0) are float, else double.
+// prepare_coarse_cycle: allow lds_bytes of dynamic LDS for the kernel (once
+// at setup, before any launch or capture).
+hipError_t prepare_coarse_cycle(int ns_max, size_t lds_bytes, int f32);
+// Static LDS of the coarse kernel (bytes), to subtract from COARSE_LDS_BYTES.
+size_t coarse_cycle_static_lds();
 void launch_coarse_cycle(hipStream_t st, const CoarseLevel* Ls, int top, int m_top, int growth, int q,
                          const void* inv0, int n0, int ns_max, int lds_doubles, int f32);
 

@@ -146,7 +146,12 @@ __global__ void __launch_bounds__(256) k_patch_relax(int np, const int* __restri
   if (on) {
     f = pf[(i / M2) * np + p];
     const int c = i % M2;
-    rs[lp][i] = f >= 0 ? b[(long)f * M2 + c] - yF[(long)(2 * f) * M2 + c] - yF[(long)(2 * f + 1) * M2 + c] : 0.0;
+    double r = 0.0;
+    if (f >= 0) {
+      r = b[(long)f * M2 + c];
+      if (yF) r -= yF[(long)(2 * f) * M2 + c] + yF[(long)(2 * f + 1) * M2 + c];
+    }
+    rs[lp][i] = r;
   }
   __syncthreads();
   if (!on) return;
@@ -188,8 +193,12 @@ __global__ void __launch_bounds__(FAST_NF * M2 * SYM_PB)
   const int p = blockIdx.x * PB + lp;
   const bool on = p < np;
   const int f = on ? pf[(i / M2) * np + p] : -1;
-  rs[i * PB + lp] =
-      f >= 0 ? b[(long)f * M2 + c] - yF[(long)(2 * f) * M2 + c] - yF[(long)(2 * f + 1) * M2 + c] : 0.0;
+  double r = 0.0;
+  if (f >= 0) {
+    r = b[(long)f * M2 + c];
+    if (yF) r -= yF[(long)(2 * f) * M2 + c] + yF[(long)(2 * f + 1) * M2 + c];
+  }
+  rs[i * PB + lp] = r;
   __syncthreads();
   if (!on) return;
   const double* Pq = Pp + p;

@@ -38,7 +38,7 @@ void launch_facet_sum(hipStream_t st, int nint, int m2, const double* yF, const 
                       double* y);
 // x_s += A_ss^-1 (b - y)_s for the np patches of one colour (Pp in the
 // layout fast_patch_words(m2, full) describes; full = false only for TS =
-// double)
+// double); yF null: y = 0
 template <typename TS>
 void launch_patch_relax(hipStream_t st, int m2, int np, const int* pf, const TS* Pp, const double* b,
                         const double* yF, double* x, bool full = true);

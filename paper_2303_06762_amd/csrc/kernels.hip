@@ -548,14 +548,28 @@ __global__ void k_spmv(int nrows, const int* __restrict__ rp, const int* __restr
 }
 
 // ELL (padded, column-major) sparse matrix-vector product: entry k of row r
-// at [k * n + r], padding has value 0 and column 0.
+// at [k * n + r], padding has value 0 and column 0.  Slots go in chunks of
+// eight, so that a thread has eight value and column loads, then eight
+// gathers, in flight at once; slots past the width re-read the last one
+// and count zero.
 template <typename TS>
 __global__ void k_ell_spmv(int n, int w, const int* __restrict__ ci, const TS* __restrict__ v,
                            const double* __restrict__ x, double* y, double beta_y) {
   int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
+  if (r >= n || w <= 0) return;
   double s = 0.0;
-  for (int k = 0; k < w; ++k) s += (double)v[(long)k * n + r] * x[ci[(long)k * n + r]];
+  for (int k0 = 0; k0 < w; k0 += 8) {
+    TS vv[8];
+    int cc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const long k = min(k0 + q, w - 1);
+      vv[q] = v[k * n + r] * (TS)(k0 + q < w);
+      cc[q] = ci[k * n + r];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) s += (double)vv[q] * x[cc[q]];
+  }
   y[r] = beta_y == 0.0 ? s : beta_y * y[r] + s;
 }
 

@@ -489,23 +489,31 @@ double phase_bytes(const hdgmg_ctx* ctx, const DevLevel& D, int level, int c) {
   return scale * (level < 0 ? ctx->relax_bytes[c] : ctx->smooth_bytes[level][c]);
 }
 
-void sweep(hdgmg_ctx* ctx, DevLevel& D, double* x, const double* b, bool forward, int level) {
+// One Gauss-Seidel sweep over the colours.  x_zero: x is zero on entry, so
+// the first colour phase of the streaming layout needs no cell apply (its
+// residual is b).
+void sweep(hdgmg_ctx* ctx, DevLevel& D, double* x, const double* b, bool forward, int level, bool x_zero = false) {
   const int nc = (int)D.colour_ptr.size() - 1;
   for (int i = 0; i < nc; ++i) {
     int c = forward ? i : nc - 1 - i;
     if (D.fast) {
       // colour phase = cell apply (all cells) + patch relaxation (colour c)
-      int t = kt_begin(ctx, level < 0 ? 1 : 2);
-      if (D.f32)
-        launch_cell_apply<float>(ctx->st, 2 * D.m, D.nc, D.Sp32, D.cdof, x, D.yF, D.full);
-      else
-        launch_cell_apply<double>(ctx->st, 2 * D.m, D.nc, D.Sp, D.cdof, x, D.yF, D.full);
-      kt_end(ctx, level < 0 ? 1 : 2, t, D.bytes_cell_vc);
+      const bool skip = x_zero && i == 0;
+      int t;
+      if (!skip) {
+        t = kt_begin(ctx, level < 0 ? 1 : 2);
+        if (D.f32)
+          launch_cell_apply<float>(ctx->st, 2 * D.m, D.nc, D.Sp32, D.cdof, x, D.yF, D.full);
+        else
+          launch_cell_apply<double>(ctx->st, 2 * D.m, D.nc, D.Sp, D.cdof, x, D.yF, D.full);
+        kt_end(ctx, level < 0 ? 1 : 2, t, D.bytes_cell_vc);
+      }
+      const double* yF = skip ? nullptr : D.yF;
       t = kt_begin(ctx, level < 0 ? 0 : 2);
       if (D.f32)
-        launch_patch_relax<float>(ctx->st, 2 * D.m, D.npc[c], D.pfc[c], D.Pp32[c], b, D.yF, x, D.pfull);
+        launch_patch_relax<float>(ctx->st, 2 * D.m, D.npc[c], D.pfc[c], D.Pp32[c], b, yF, x, D.pfull);
       else
-        launch_patch_relax<double>(ctx->st, 2 * D.m, D.npc[c], D.pfc[c], D.Ppc[c], b, D.yF, x, D.pfull);
+        launch_patch_relax<double>(ctx->st, 2 * D.m, D.npc[c], D.pfc[c], D.Ppc[c], b, yF, x, D.pfull);
       kt_end(ctx, level < 0 ? 0 : 2, t, D.bytes_relax_vc[c]);
     } else if (D.rec) {
       int t = kt_begin(ctx, 2);
@@ -556,8 +564,9 @@ void apply_k(hdgmg_ctx* ctx, const double* x, double* y, double alpha, const dou
   level_apply(ctx, ctx->K, x, y, alpha, b, 1, vc);
 }
 
-// Alg. 1 on lowest-order level l: u_l <- MG_h(l, g_l, u_l, m_l, q)
-void mg_h(hdgmg_ctx* ctx, int l, int m_l) {
+// Alg. 1 on lowest-order level l: u_l <- MG_h(l, g_l, u_l, m_l, q); u_zero:
+// u_l is zero on entry.
+void mg_h(hdgmg_ctx* ctx, int l, int m_l, bool u_zero) {
   DevLevel& D = ctx->cr[l];
   if (l <= ctx->Lc) {
     int t = kt_begin(ctx, 4);
@@ -575,7 +584,7 @@ void mg_h(hdgmg_ctx* ctx, int l, int m_l) {
       launch_gemv_dense<double>(ctx->st, ctx->n0, ctx->coarse_inv, D.g, D.u);
     return;
   }
-  for (int s = 0; s < m_l; ++s) sweep(ctx, D, D.u, D.g, true, l);
+  for (int s = 0; s < m_l; ++s) sweep(ctx, D, D.u, D.g, true, l, u_zero && s == 0);
   level_apply(ctx, D, D.u, D.r, -1.0, D.g, 2, true);
   DevTransfer& T = ctx->tr[l];
   DevLevel& C = ctx->cr[l - 1];
@@ -584,7 +593,7 @@ void mg_h(hdgmg_ctx* ctx, int l, int m_l) {
   else
     launch_ell_spmv<double>(ctx->st, T.ncoarse, T.Rw, T.Re_ci, T.Re_v, D.r, C.g, 0.0);
   launch_fill(ctx->st, C.ndof, 0.0, C.u);
-  for (int n = 0; n < ctx->opts.cycle; ++n) mg_h(ctx, l - 1, ctx->opts.vcycle_growth * m_l);
+  for (int n = 0; n < ctx->opts.cycle; ++n) mg_h(ctx, l - 1, ctx->opts.vcycle_growth * m_l, n == 0);
   if (ctx->opts.vcycle_precision == 1)
     launch_ell_spmv<float>(ctx->st, T.nfine, T.Pw, T.Pe_ci, T.Pe_v32, C.u, D.u, 1.0);
   else
@@ -647,16 +656,16 @@ void mg_hp_body(hdgmg_ctx* ctx, const double* r, double* z) {
   if (ctx->k == 0) {
     launch_copy(ctx->st, DJ.ndof, r, DJ.g);
     launch_fill(ctx->st, DJ.ndof, 0.0, DJ.u);
-    mg_h(ctx, ctx->J - 1, ctx->opts.m_smooth);
+    mg_h(ctx, ctx->J - 1, ctx->opts.m_smooth, true);
     launch_copy(ctx->st, DJ.ndof, DJ.u, z);
     return;
   }
   launch_fill(ctx->st, KL.ndof, 0.0, z);
-  for (int s = 0; s < ctx->opts.m_relax; ++s) sweep(ctx, KL, z, r, true, -1);
+  for (int s = 0; s < ctx->opts.m_relax; ++s) sweep(ctx, KL, z, r, true, -1, s == 0);
   apply_k(ctx, z, KL.r, -1.0, r, true);
   launch_mode0_extract(ctx->st, KL.nint, KL.m, KL.r, DJ.g);
   launch_fill(ctx->st, DJ.ndof, 0.0, DJ.u);
-  mg_h(ctx, ctx->J - 1, ctx->opts.m_smooth);
+  mg_h(ctx, ctx->J - 1, ctx->opts.m_smooth, true);
   launch_mode0_add(ctx->st, KL.nint, KL.m, DJ.u, z);
   for (int s = 0; s < ctx->opts.m_relax; ++s) sweep(ctx, KL, z, r, false, -1);
 }
@@ -1030,6 +1039,7 @@ hdgmg_status build_coarse(hdgmg_ctx* ctx) {
     off += 3 * n;
     C.u_glob = D.u;
     C.g_glob = D.g;
+    C.lds_meta = C.lds_val = C.lds_ainv = -1;
     if (l == 0) continue;
     LevelRecords R;
     TRY(level_records(ctx, l, COARSE_THREADS, R));
@@ -1064,6 +1074,31 @@ hdgmg_status build_coarse(hdgmg_ctx* ctx) {
     C.P_w = T.Pw;
     C.P_ci = T.Pe_ci;
     C.P_v = f32 ? (const void*)T.Pe_v32 : (const void*)T.Pe_v;
+  }
+  // Record parts that stay in LDS for the whole kernel, coarsest levels
+  // first (they have the most sweeps): residual rows before inverse rows.
+  {
+    const bool f32 = ctx->opts.vcycle_precision == 1;
+    const size_t G = f32 ? 4 : 2;
+    const size_t cap = COARSE_LDS_BYTES - coarse_cycle_static_lds() - 256;
+    size_t bytes = ((size_t)off * sizeof(double) + 15) / 16 * 16;
+    for (int l = 1; l <= Lc; ++l) {
+      CoarseLevel& C = desc[l];
+      const size_t nit = C.nitems;
+      const size_t mb = 32 * nit, vb = (COARSE_NNZ + G - 1) / G * 16 * nit;
+      const size_t ab = (std::max(C.ns_max, 1) + G - 1) / G * 16 * nit;
+      if (bytes + mb + vb <= cap) {
+        C.lds_meta = (int)bytes;
+        C.lds_val = (int)(bytes + mb);
+        bytes += mb + vb;
+        if (bytes + ab <= cap) {
+          C.lds_ainv = (int)bytes;
+          bytes += ab;
+        }
+      }
+    }
+    off = (int)((bytes + sizeof(double) - 1) / sizeof(double));
+    HIPC(prepare_coarse_cycle(nsmax, (size_t)off * sizeof(double), f32 ? 1 : 0));
   }
   std::vector<char> raw(sizeof(CoarseLevel) * desc.size());
   std::memcpy(raw.data(), desc.data(), raw.size());
@@ -1445,10 +1480,14 @@ hdgmg_status hdgmg_assemble(hdgmg_ctx* ctx) {
   {
     const auto& o = ctx->opts;
     double v = 0.0;
+    // (the first colour phase from a zero iterate has no cell apply)
     if (ctx->k > 0) {
+      const DevLevel& K = ctx->K;
       double sw = 0.0;
-      for (int c = 0; c < (int)ctx->K.colour_ptr.size() - 1; ++c) sw += phase_bytes(ctx, ctx->K, -1, c);
-      v += 2.0 * o.m_relax * sw + 2.0 * ctx->K.ndof * 8.0;  // sweeps; the mode-0 transfers
+      for (int c = 0; c < (int)K.colour_ptr.size() - 1; ++c) sw += phase_bytes(ctx, K, -1, c);
+      const double res = K.fast ? K.bytes_cell_vc + K.bytes_sum : ctx->apply_bytes * (K.f32 ? 0.5 : 1.0);
+      v += 2.0 * o.m_relax * sw - (K.fast ? K.bytes_cell_vc : 0.0) + res;  // sweeps, residual
+      v += 2.0 * K.ndof * 8.0;                                                 // the mode-0 transfers
     }
     double visits = 1.0, m_l = o.m_smooth;
     for (int l = ctx->J - 1; l >= 1; --l) {
@@ -1459,7 +1498,8 @@ hdgmg_status hdgmg_assemble(hdgmg_ctx* ctx) {
       double res = D.fast ? D.bytes_cell_vc + D.bytes_sum
                           : (double)D.nc * 36 * ws + (D.nc * 6.0 + 2.0 * D.ndof) * 8.0;
       double trn = 2.0 * (ctx->tr[l].nnz * (4.0 + ws) + (ctx->tr[l].nfine + ctx->tr[l].ncoarse) * 8.0);
-      v += visits * (2.0 * m_l * sw + res + trn);
+      const double zero_starts = l == ctx->J - 1 ? 1.0 : visits / o.cycle;
+      v += visits * (2.0 * m_l * sw + res + trn) - (D.fast ? zero_starts * D.bytes_cell_vc : 0.0);
       visits *= o.cycle;
       m_l *= o.vcycle_growth;
     }
