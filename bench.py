@@ -38,8 +38,8 @@ ROOF_CLASS = 1
 # what the counter read for a plain copy of 1 GiB in the same run (FETCH
 # 524308 KiB -> x2.0, WRITE 1048576 KiB -> x1.0).  Valid only for the
 # workload and kernel it was taken on.
-TRAFFIC = {(2, 6, 1.0, 1e2): {"kernel": "k_cell_apply<6, double>", "fetch_KiB": 95685.79,
-                              "write_KiB": 18770.71, "fetch_scale": 1048576 / 524308.0,
+TRAFFIC = {(2, 6, 1.0, 1e2): {"kernel": "k_cell_apply<6, double>", "fetch_KiB": 101245.78,
+                              "write_KiB": 18780.79, "fetch_scale": 1048576 / 524308.31,
                               "write_scale": 1.0}}
 
 
