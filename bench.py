@@ -258,6 +258,7 @@ def main():
 
     m64 = measure(0)
     m32 = measure(1)
+    m16 = measure(2)
     tm = m64["tm"]
     dom = ROOF_CLASS
     ms, n_l, by = tm[dom]
@@ -299,6 +300,14 @@ def main():
                                "flexible CG FP64; same rel.res 1e-8 on the FP64 operator",
                   "vcycle_avg_ms": m32["tm"][3][0] / max(m32["tm"][3][1], 1),
                   "kernel_classes": classes(m32["tm"])},
+        "mixed_fp16": {"value": n_skel * a.steps / m16["T"], "unit": "skeleton DOFs/s",
+                       "ms_per_step": 1e3 * m16["T"] / a.steps, "iterations": m16["its"],
+                       "precision": "order-k cell blocks (augmented-Lagrangian term kept apart in FP32) "
+                                    "and patch inverses stored FP16, each block scaled by its largest "
+                                    "magnitude; other V-cycle operators FP32; vectors, accumulation and "
+                                    "the flexible CG FP64; same rel.res 1e-8 on the FP64 operator",
+                       "vcycle_avg_ms": m16["tm"][3][0] / max(m16["tm"][3][1], 1),
+                       "kernel_classes": classes(m16["tm"])},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "kernel": KCLASS[dom], "launches": n_l, "avg_us": 1e3 * ms / n_l,

@@ -95,8 +95,12 @@ typedef struct {
                               vertex patches of at most 6 facets) use the
                               streaming cell-apply / patch-relax kernels   */
   int vcycle_precision;    /* storage of every operator the preconditioner
-                              reads: 0 FP64, 1 FP32 (vectors, accumulation
-                              and the outer Krylov solver stay FP64)       */
+                              reads: 0 FP64, 1 FP32, 2 FP32 with the
+                              order-k level's streaming cell blocks (k <= 2,
+                              symmetric) and patch inverses in FP16, each
+                              block scaled by its largest magnitude
+                              (vectors, accumulation and the outer Krylov
+                              solver stay FP64)                           */
   int oseen;               /* 1: the context solves Picard-linearised
                               (Oseen) systems (Sec. 4): hdgmg_set_wind is
                               allowed, every block and patch factor is

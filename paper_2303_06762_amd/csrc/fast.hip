@@ -50,10 +50,22 @@ struct Grp<float> {
   static constexpr int G = 4;
   __device__ static float get(const float4& v, int i) { return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w; }
 };
+template <>
+struct Grp<_Float16> {
+  using T = _Float16 __attribute__((ext_vector_type(8)));
+  static constexpr int G = 8;
+  __device__ static float get(const T& v, int i) { return (float)v[i]; }
+};
 
+// al: FP16 blocks only (else null), per cell (s, c0, c1, c2): the stored
+// block is S0_K / s, where S0_K is S_K without the augmented-Lagrangian term
+// c c^T on the mode-0 normal unknowns (c_i = sqrt(eps^-1 / |K|) sigma_i |F_i|)
+// and without the rows and columns of boundary facets; the term is applied
+// here from c.
 template <int M2, typename TS>
 __global__ void __launch_bounds__(256) k_cell_apply(int nc, const TS* __restrict__ Sp, const int* __restrict__ cdof,
-                                                    const double* __restrict__ x, double* __restrict__ yF) {
+                                                    const double* __restrict__ x, double* __restrict__ yF,
+                                                    const float4* __restrict__ al) {
   constexpr int NK = 3 * M2;
   using GT = Grp<TS>;
   using V = typename GT::T;
@@ -86,6 +98,15 @@ __global__ void __launch_bounds__(256) k_cell_apply(int nc, const TS* __restrict
       yl[a] += s * xl[b];
       if (b != a) yl[b] += s * xl[a];
     }
+  }
+  if (al) {
+    const float4 w = al[K];
+    const double c[3] = {(double)w.y, (double)w.z, (double)w.w};
+    const double dx = c[0] * xl[0] + c[1] * xl[M2] + c[2] * xl[2 * M2];
+#pragma unroll
+    for (int a = 0; a < NK; ++a) yl[a] *= (double)w.x;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) yl[i * M2] += c[i] * dx;
   }
 #pragma unroll
   for (int i = 0; i < 3; ++i)
@@ -133,10 +154,11 @@ __global__ void __launch_bounds__(256) k_cell_apply_rows(int nc, const TS* __res
 
 // x_s += A_ss^-1 (b - y)_s for the patches of one colour: a thread per
 // (patch, row), the patch residual shared through LDS.
+// sc: per-patch scale of FP16 inverses, else null.
 template <int M2, typename TS>
 __global__ void __launch_bounds__(256) k_patch_relax(int np, const int* __restrict__ pf, const TS* __restrict__ Pp,
                                                      const double* __restrict__ b, const double* __restrict__ yF,
-                                                     double* __restrict__ x) {
+                                                     double* __restrict__ x, const float* __restrict__ sc) {
   constexpr int NS = FAST_NF * M2, PPB = 256 / NS;
   __shared__ double rs[PPB][NS];
   const int lp = threadIdx.x / NS, i = threadIdx.x % NS;
@@ -162,6 +184,7 @@ __global__ void __launch_bounds__(256) k_patch_relax(int np, const int* __restri
     d += (double)*q * rs[lp][j];
     q += (long)np * NS;
   }
+  if (sc) d *= (double)sc[p];
   if (f >= 0) x[(long)f * M2 + i % M2] += d;
 }
 
@@ -231,6 +254,58 @@ __global__ void k_regroup_f32(int nc, long nw, const double* __restrict__ Sp, fl
   Sp32[((e / 4) * nc + K) * 4 + e % 4] = (float)Sp[((e / 2) * nc + K) * 2 + e % 2];
 }
 
+// FP64 pair-grouped packed blocks -> FP16 groups of eight (the layout
+// k_cell_apply<M2, _Float16> reads): the augmented-Lagrangian term and the
+// boundary rows and columns removed, the rest divided by its largest
+// magnitude; al[K] = (that magnitude, c0, c1, c2).  cdiv: sigma |F| per
+// (cell, local facet), 0 on the boundary; area: |K|.
+__global__ void k_regroup_f16(int nc, int m2, const double* __restrict__ Sp, const int* __restrict__ cdof,
+                              const double* __restrict__ cdiv, const double* __restrict__ area, double eps_inv,
+                              _Float16* __restrict__ Sp16, float4* __restrict__ al) {
+  const int K = blockIdx.x * blockDim.x + threadIdx.x;
+  if (K >= nc) return;
+  const int nK = 3 * m2;
+  const double w = eps_inv / area[K];
+  double dv[3];
+  bool in[3];
+  for (int i = 0; i < 3; ++i) {
+    dv[i] = cdiv[3 * K + i];
+    in[i] = cdof[i * nc + K] >= 0;
+  }
+  auto value = [&](int a, int b, long e) {
+    const int fa = a / m2, fb = b / m2;
+    if (!in[fa] || !in[fb]) return 0.0;
+    double v = Sp[((e / 2) * nc + K) * 2 + e % 2];
+    if (a % m2 == 0 && b % m2 == 0) v -= w * dv[fa] * dv[fb];
+    return v;
+  };
+  double mx = 0.0;
+  long e = 0;
+  for (int a = 0; a < nK; ++a)
+    for (int b = a; b < nK; ++b, ++e) mx = fmax(mx, fabs(value(a, b, e)));
+  const double f = mx > 0.0 ? mx : 1.0;
+  const double sw = sqrt(w);
+  al[K] = make_float4((float)f, (float)(sw * dv[0]), (float)(sw * dv[1]), (float)(sw * dv[2]));
+  e = 0;
+  for (int a = 0; a < nK; ++a)
+    for (int b = a; b < nK; ++b, ++e) Sp16[((e / 8) * nc + K) * 8 + e % 8] = (_Float16)(value(a, b, e) / f);
+}
+
+// FP64 full patch inverses ([j][p][i]) -> FP16, each divided by its largest
+// magnitude (kept in sc[p]).
+__global__ void k_patches_f16(int np, int ns, const double* __restrict__ Pp, _Float16* __restrict__ P16,
+                              float* __restrict__ sc) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  double mx = 0.0;
+  for (int j = 0; j < ns; ++j)
+    for (int i = 0; i < ns; ++i) mx = fmax(mx, fabs(Pp[((long)j * np + p) * ns + i]));
+  const double f = mx > 0.0 ? mx : 1.0;
+  sc[p] = (float)f;
+  for (int j = 0; j < ns; ++j)
+    for (int i = 0; i < ns; ++i) P16[((long)j * np + p) * ns + i] = (_Float16)(Pp[((long)j * np + p) * ns + i] / f);
+}
+
 // Full row-major cell blocks -> [b][K][a] SoA.
 template <typename TS>
 __global__ void k_pack_cells_full(int nc, int nK, const double* __restrict__ S, TS* __restrict__ Sf) {
@@ -279,7 +354,7 @@ inline int nblk(long n, int t = 256) { return (int)((n + t - 1) / t); }
 
 template <typename TS>
 void cell_apply_t(hipStream_t st, int m2, int nc, const TS* Sp, const int* cdof, const double* x, double* yF,
-                  bool full) {
+                  bool full, const float4* sc) {
   if (!fast_cell_packed(3 * m2, full)) {
     switch (m2) {
 #define CASE(M)                                                                                        \
@@ -295,7 +370,7 @@ void cell_apply_t(hipStream_t st, int m2, int nc, const TS* Sp, const int* cdof,
   switch (m2) {
 #define CASE(M)                                                                                  \
   case M:                                                                                        \
-    hipLaunchKernelGGL((k_cell_apply<M, TS>), dim3(nblk(nc)), dim3(256), 0, st, nc, Sp, cdof, x, yF); \
+    hipLaunchKernelGGL((k_cell_apply<M, TS>), dim3(nblk(nc)), dim3(256), 0, st, nc, Sp, cdof, x, yF, sc); \
     break;
     CASE(2) CASE(4) CASE(6)
 #undef CASE
@@ -304,7 +379,7 @@ void cell_apply_t(hipStream_t st, int m2, int nc, const TS* Sp, const int* cdof,
 
 template <typename TS>
 void patch_relax_t(hipStream_t st, int m2, int np, const int* pf, const TS* Pp, const double* b, const double* yF,
-                   double* x, bool full) {
+                   double* x, bool full, const float* sc) {
   if constexpr (std::is_same<TS, double>::value) {
     if (!full) {
       switch (m2) {
@@ -323,7 +398,7 @@ void patch_relax_t(hipStream_t st, int m2, int np, const int* pf, const TS* Pp, 
 #define CASE(M)                                                                                            \
   case M:                                                                                                  \
     hipLaunchKernelGGL((k_patch_relax<M, TS>), dim3((np + 256 / (6 * M) - 1) / (256 / (6 * M))), dim3(256), 0, \
-                       st, np, pf, Pp, b, yF, x);                                                       \
+                       st, np, pf, Pp, b, yF, x, sc);                                                   \
     break;
     CASE(2) CASE(4) CASE(6) CASE(8) CASE(10)
 #undef CASE
@@ -334,13 +409,15 @@ void patch_relax_t(hipStream_t st, int m2, int np, const int* pf, const TS* Pp, 
 
 template <typename TS>
 void launch_cell_apply(hipStream_t st, int m2, int nc, const TS* Sp, const int* cdof, const double* x,
-                       double* yF, bool full) {
-  if (nc > 0) cell_apply_t<TS>(st, m2, nc, Sp, cdof, x, yF, full);
+                       double* yF, bool full, const float4* al) {
+  if (nc > 0) cell_apply_t<TS>(st, m2, nc, Sp, cdof, x, yF, full, al);
 }
 template void launch_cell_apply<double>(hipStream_t, int, int, const double*, const int*, const double*, double*,
-                                        bool);
+                                        bool, const float4*);
 template void launch_cell_apply<float>(hipStream_t, int, int, const float*, const int*, const double*, double*,
-                                       bool);
+                                       bool, const float4*);
+template void launch_cell_apply<_Float16>(hipStream_t, int, int, const _Float16*, const int*, const double*,
+                                          double*, bool, const float4*);
 
 void launch_facet_sum(hipStream_t st, int nint, int m2, const double* yF, const double* b, double alpha,
                       double* y) {
@@ -350,13 +427,27 @@ void launch_facet_sum(hipStream_t st, int nint, int m2, const double* yF, const 
 
 template <typename TS>
 void launch_patch_relax(hipStream_t st, int m2, int np, const int* pf, const TS* Pp, const double* b,
-                        const double* yF, double* x, bool full) {
-  if (np > 0) patch_relax_t<TS>(st, m2, np, pf, Pp, b, yF, x, full);
+                        const double* yF, double* x, bool full, const float* sc) {
+  if (np > 0) patch_relax_t<TS>(st, m2, np, pf, Pp, b, yF, x, full, sc);
 }
 template void launch_patch_relax<double>(hipStream_t, int, int, const int*, const double*, const double*,
-                                         const double*, double*, bool);
+                                         const double*, double*, bool, const float*);
 template void launch_patch_relax<float>(hipStream_t, int, int, const int*, const float*, const double*,
-                                        const double*, double*, bool);
+                                        const double*, double*, bool, const float*);
+template void launch_patch_relax<_Float16>(hipStream_t, int, int, const int*, const _Float16*, const double*,
+                                           const double*, double*, bool, const float*);
+
+void launch_cells_f16(hipStream_t st, int nc, int m2, const double* Sp, const int* cdof, const double* cdiv,
+                      const double* area, double eps_inv, _Float16* Sp16, float4* al) {
+  if (nc > 0)
+    hipLaunchKernelGGL(k_regroup_f16, dim3(nblk(nc)), dim3(256), 0, st, nc, m2, Sp, cdof, cdiv, area, eps_inv, Sp16,
+                       al);
+}
+
+void launch_patches_f16(hipStream_t st, int np, int m2, const double* Pp, _Float16* P16, float* sc) {
+  if (np > 0)
+    hipLaunchKernelGGL(k_patches_f16, dim3(nblk(np)), dim3(256), 0, st, np, FAST_NF * m2, Pp, P16, sc);
+}
 
 void launch_regroup_cells_f32(hipStream_t st, int nc, int nK, const double* Sp, float* Sp32) {
   const long nw = (long)nK * (nK + 1) / 2;

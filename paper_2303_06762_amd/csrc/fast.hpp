@@ -15,10 +15,12 @@ constexpr int FAST_NF = 6;
 // the nonsymmetric blocks of the Oseen operator).
 inline bool fast_cell_packed(int nK, bool full) { return nK <= 18 && !full; }
 // Packed blocks are stored in 16-byte groups (pairs of doubles, quads of
-// floats): room for the words rounded up to a multiple of 4.
+// floats): room for the words rounded up to a multiple of 4.  The FP16 copy
+// (groups of eight halves) holds fast_cell_words16 halves per cell.
 inline long fast_cell_words(int nK, bool full = false) {
   return fast_cell_packed(nK, full) ? ((long)nK * (nK + 1) / 2 + 3) / 4 * 4 : (long)nK * nK;
 }
+inline long fast_cell_words16(int nK) { return ((long)nK * (nK + 1) / 2 + 7) / 8 * 8; }
 
 // Patch-inverse storage: the upper triangle of each zero-padded FAST_NF*m2
 // square inverse (full = false: symmetric operators, FP64 only), else the
@@ -30,9 +32,11 @@ inline long fast_patch_words(int m2, bool full) {
 
 // y_F[(2F+side)*m2 + c] = rows of S_K x_K for every cell K (m2 = 2 modes
 // per facet component x 2 components).
+// TS = _Float16 (packed blocks only): al[K] = (s, c0, c1, c2) as
+// launch_cells_f16 writes it; else al is null.
 template <typename TS>
 void launch_cell_apply(hipStream_t st, int m2, int nc, const TS* Sp, const int* cdof, const double* x,
-                       double* yF, bool full = false);
+                       double* yF, bool full = false, const float4* al = nullptr);
 // y = b + alpha * (y_F[side 0] + y_F[side 1]) (b may be null)
 void launch_facet_sum(hipStream_t st, int nint, int m2, const double* yF, const double* b, double alpha,
                       double* y);
@@ -41,11 +45,20 @@ void launch_facet_sum(hipStream_t st, int nint, int m2, const double* yF, const 
 // double); yF null: y = 0
 template <typename TS>
 void launch_patch_relax(hipStream_t st, int m2, int np, const int* pf, const TS* Pp, const double* b,
-                        const double* yF, double* x, bool full = true);
+                        const double* yF, double* x, bool full = true, const float* sc = nullptr);
 void launch_pack_cells(hipStream_t st, int nc, int nK, const double* S, double* Sp, bool full = false);
 // FP32 copy of packed blocks (pair groups -> quad groups).
 void launch_regroup_cells_f32(hipStream_t st, int nc, int nK, const double* Sp, float* Sp32);
 void launch_pack_patches(hipStream_t st, int np, int gp0, int m2, const int* pf_ptr, const long* pinv_off,
                          const double* pinv, double* Pp, bool full = true);
+// FP16 copies for the half-precision V-cycle storage.  Packed cell blocks
+// (FP64 pair groups -> groups of eight): S0_K = S_K without its
+// augmented-Lagrangian term eps^-1 |K|^-1 d d^T (d_i = cdiv[3K+i] on the
+// mode-0 normal unknowns) and without boundary rows and columns, divided by
+// its largest magnitude s; al[K] = (s, sqrt(eps^-1/|K|) d_0, .. d_1, .. d_2).
+// Full patch inverses: each divided by its largest magnitude (sc: np floats).
+void launch_cells_f16(hipStream_t st, int nc, int m2, const double* Sp, const int* cdof, const double* cdiv,
+                      const double* area, double eps_inv, _Float16* Sp16, float4* al);
+void launch_patches_f16(hipStream_t st, int np, int m2, const double* Pp, _Float16* P16, float* sc);
 
 }  // namespace hdgmg

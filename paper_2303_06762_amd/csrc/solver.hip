@@ -80,6 +80,13 @@ struct DevLevel {
   bool f32 = false;
   float *S32 = nullptr, *pinv32 = nullptr, *Sp32 = nullptr;
   std::vector<float*> Pp32;
+  // FP16 copies of the streaming operators of the order-k level
+  // (vcycle_precision 2), each block divided by its largest magnitude
+  bool f16 = false;
+  _Float16* Sp16 = nullptr;
+  float4* al16 = nullptr;
+  std::vector<_Float16*> Pp16;
+  std::vector<float*> psc16;
   double bytes_cell_vc = 0.0;
   std::vector<double> bytes_relax_vc;
   template <typename TS>
@@ -215,6 +222,10 @@ struct hdgmg_ctx {
   std::vector<std::vector<double>> smooth_bytes;  // lowest-order levels
   double apply_bytes = 0.0, vcycle_bytes = 0.0;
 };
+
+// The preconditioner reads FP32 (vcycle_precision 1) or FP32 with FP16
+// order-k blocks (2) copies of its operators.
+inline bool vc_f32(const hdgmg_ctx* ctx) { return ctx->opts.vcycle_precision >= 1; }
 
 namespace {
 
@@ -373,7 +384,7 @@ hdgmg_status upload_level(hdgmg_ctx* ctx, const Level& L, int m, DevLevel& D) {
     // per interior facet, y_F once per (cell, interior facet)
     const double vec = ((double)L.nint + ncd) * m2 * 8.0 + L.nc * 12.0;
     D.bytes_cell = (double)L.nc * D.sp_words * 8.0 + vec;
-    const double ws = ctx->opts.vcycle_precision == 1 ? 4.0 : 8.0;
+    const double ws = vc_f32(ctx) ? 4.0 : 8.0;
     D.bytes_cell_vc = (double)L.nc * D.sp_words * ws + vec;
     D.bytes_sum = 3.0 * L.nint * m2 * 8.0;
     // symmetric FP64 patch inverses are stored as upper triangles, addressed
@@ -381,7 +392,7 @@ hdgmg_status upload_level(hdgmg_ctx* ctx, const Level& L, int m, DevLevel& D) {
     // their streaming relaxation is faster than the triangular one)
     int np_max = 0;
     for (int cc = 0; cc < L.ncol; ++cc) np_max = std::max(np_max, L.colour_ptr[cc + 1] - L.colour_ptr[cc]);
-    D.pfull = D.full || ctx->opts.vcycle_precision == 1 ||
+    D.pfull = D.full || vc_f32(ctx) ||
               (long)np_max * fast_patch_words(m2, false) >= (1L << 31);
     const long pw = fast_patch_words(m2, D.pfull);
     for (int cc = 0; cc < L.ncol; ++cc) {
@@ -445,9 +456,11 @@ hdgmg_status pack_fast(hdgmg_ctx* ctx, DevLevel& D) {
   return HDGMG_OK;
 }
 
-// FP32 copies of the operators a level's smoothing and residuals read.
-hdgmg_status make_f32(hdgmg_ctx* ctx, DevLevel& D) {
-  if (ctx->opts.vcycle_precision != 1) return HDGMG_OK;
+// FP32 copies of the operators a level's smoothing and residuals read;
+// with vcycle_precision 2, FP16 copies of the order-k level's streaming
+// operators (packed cell blocks and full patch inverses) as well.
+hdgmg_status make_f32(hdgmg_ctx* ctx, DevLevel& D, bool order_k = false) {
+  if (!vc_f32(ctx)) return HDGMG_OK;
   D.f32 = true;
   long nS = (long)D.nc * D.nK * D.nK;
   TRY(dalloc(ctx, &D.S32, (size_t)nS));
@@ -467,6 +480,25 @@ hdgmg_status make_f32(hdgmg_ctx* ctx, DevLevel& D) {
       long n = std::max(D.npc[c], 1) * pw;
       TRY(dalloc(ctx, &D.Pp32[c], (size_t)n));
       launch_to_f32(ctx->st, n, D.Ppc[c], D.Pp32[c]);
+    }
+    if (order_k && ctx->opts.vcycle_precision == 2 && fast_cell_packed(D.nK, D.full) && D.pfull) {
+      D.f16 = true;
+      TRY(dalloc(ctx, &D.Sp16, (size_t)D.nc * fast_cell_words16(D.nK)));
+      TRY(dalloc(ctx, &D.al16, (size_t)D.nc));
+      launch_cells_f16(ctx->st, D.nc, 2 * D.m, D.Sp, D.cdof, ctx->cdiv, ctx->area, ctx->gamma, D.Sp16, D.al16);
+      D.Pp16.assign(D.Ppc.size(), nullptr);
+      D.psc16.assign(D.Ppc.size(), nullptr);
+      for (size_t c = 0; c < D.Ppc.size(); ++c) {
+        const int np = std::max(D.npc[c], 1);
+        TRY(dalloc(ctx, &D.Pp16[c], (size_t)np * pw));
+        TRY(dalloc(ctx, &D.psc16[c], (size_t)np));
+        launch_patches_f16(ctx->st, D.npc[c], 2 * D.m, D.Ppc[c], D.Pp16[c], D.psc16[c]);
+      }
+      // the preconditioner's bytes: halves plus one scale per block
+      const double vec = D.bytes_cell_vc - (double)D.nc * D.sp_words * 4.0;
+      D.bytes_cell_vc = (double)D.nc * (fast_cell_words16(D.nK) * 2.0 + 16.0) + vec;
+      for (size_t c = 0; c < D.bytes_relax_vc.size(); ++c)
+        D.bytes_relax_vc[c] -= (double)D.npc[c] * pw * 2.0 - (double)D.npc[c] * 4.0;
     }
   }
   HIPC(hipGetLastError());
@@ -502,7 +534,9 @@ void sweep(hdgmg_ctx* ctx, DevLevel& D, double* x, const double* b, bool forward
       int t;
       if (!skip) {
         t = kt_begin(ctx, level < 0 ? 1 : 2);
-        if (D.f32)
+        if (D.f16)
+          launch_cell_apply<_Float16>(ctx->st, 2 * D.m, D.nc, D.Sp16, D.cdof, x, D.yF, false, D.al16);
+        else if (D.f32)
           launch_cell_apply<float>(ctx->st, 2 * D.m, D.nc, D.Sp32, D.cdof, x, D.yF, D.full);
         else
           launch_cell_apply<double>(ctx->st, 2 * D.m, D.nc, D.Sp, D.cdof, x, D.yF, D.full);
@@ -510,7 +544,9 @@ void sweep(hdgmg_ctx* ctx, DevLevel& D, double* x, const double* b, bool forward
       }
       const double* yF = skip ? nullptr : D.yF;
       t = kt_begin(ctx, level < 0 ? 0 : 2);
-      if (D.f32)
+      if (D.f16)
+        launch_patch_relax<_Float16>(ctx->st, 2 * D.m, D.npc[c], D.pfc[c], D.Pp16[c], b, yF, x, true, D.psc16[c]);
+      else if (D.f32)
         launch_patch_relax<float>(ctx->st, 2 * D.m, D.npc[c], D.pfc[c], D.Pp32[c], b, yF, x, D.pfull);
       else
         launch_patch_relax<double>(ctx->st, 2 * D.m, D.npc[c], D.pfc[c], D.Ppc[c], b, yF, x, D.pfull);
@@ -539,7 +575,9 @@ void level_apply(hdgmg_ctx* ctx, DevLevel& D, const double* x, double* y, double
   const bool f32 = vc && D.f32;
   if (D.fast) {
     int t = kt_begin(ctx, cls);
-    if (f32)
+    if (vc && D.f16)
+      launch_cell_apply<_Float16>(ctx->st, 2 * D.m, D.nc, D.Sp16, D.cdof, x, D.yF, false, D.al16);
+    else if (f32)
       launch_cell_apply<float>(ctx->st, 2 * D.m, D.nc, D.Sp32, D.cdof, x, D.yF, D.full);
     else
       launch_cell_apply<double>(ctx->st, 2 * D.m, D.nc, D.Sp, D.cdof, x, D.yF, D.full);
@@ -570,7 +608,7 @@ void mg_h(hdgmg_ctx* ctx, int l, int m_l, bool u_zero) {
   DevLevel& D = ctx->cr[l];
   if (l <= ctx->Lc) {
     int t = kt_begin(ctx, 4);
-    const bool f32 = ctx->opts.vcycle_precision == 1;
+    const bool f32 = vc_f32(ctx);
     launch_coarse_cycle(ctx->st, ctx->coarse_desc, l, m_l, ctx->opts.vcycle_growth, ctx->opts.cycle,
                         f32 ? (const void*)ctx->coarse_inv32 : (const void*)ctx->coarse_inv, ctx->n0,
                         ctx->coarse_ns, ctx->coarse_lds, f32 ? 1 : 0);
@@ -578,7 +616,7 @@ void mg_h(hdgmg_ctx* ctx, int l, int m_l, bool u_zero) {
     return;
   }
   if (l == 0) {
-    if (ctx->opts.vcycle_precision == 1)
+    if (vc_f32(ctx))
       launch_gemv_dense<float>(ctx->st, ctx->n0, ctx->coarse_inv32, D.g, D.u);
     else
       launch_gemv_dense<double>(ctx->st, ctx->n0, ctx->coarse_inv, D.g, D.u);
@@ -588,13 +626,13 @@ void mg_h(hdgmg_ctx* ctx, int l, int m_l, bool u_zero) {
   level_apply(ctx, D, D.u, D.r, -1.0, D.g, 2, true);
   DevTransfer& T = ctx->tr[l];
   DevLevel& C = ctx->cr[l - 1];
-  if (ctx->opts.vcycle_precision == 1)
+  if (vc_f32(ctx))
     launch_ell_spmv<float>(ctx->st, T.ncoarse, T.Rw, T.Re_ci, T.Re_v32, D.r, C.g, 0.0);
   else
     launch_ell_spmv<double>(ctx->st, T.ncoarse, T.Rw, T.Re_ci, T.Re_v, D.r, C.g, 0.0);
   launch_fill(ctx->st, C.ndof, 0.0, C.u);
   for (int n = 0; n < ctx->opts.cycle; ++n) mg_h(ctx, l - 1, ctx->opts.vcycle_growth * m_l, n == 0);
-  if (ctx->opts.vcycle_precision == 1)
+  if (vc_f32(ctx))
     launch_ell_spmv<float>(ctx->st, T.nfine, T.Pw, T.Pe_ci, T.Pe_v32, C.u, D.u, 1.0);
   else
     launch_ell_spmv<double>(ctx->st, T.nfine, T.Pw, T.Pe_ci, T.Pe_v, C.u, D.u, 1.0);
@@ -872,11 +910,11 @@ hdgmg_status build_transfers(hdgmg_ctx* ctx) {
     to_ell(P, Tt.Pw, eci, ev);
     TRY(upload(ctx, &Tt.Pe_ci, eci));
     TRY(upload(ctx, &Tt.Pe_v, ev));
-    if (ctx->opts.vcycle_precision == 1) TRY(upload_f32(ctx, &Tt.Pe_v32, ev));
+    if (vc_f32(ctx)) TRY(upload_f32(ctx, &Tt.Pe_v32, ev));
     to_ell(R, Tt.Rw, eci, ev);
     TRY(upload(ctx, &Tt.Re_ci, eci));
     TRY(upload(ctx, &Tt.Re_v, ev));
-    if (ctx->opts.vcycle_precision == 1) TRY(upload_f32(ctx, &Tt.Re_v32, ev));
+    if (vc_f32(ctx)) TRY(upload_f32(ctx, &Tt.Re_v32, ev));
   }
   std::vector<double> inv;
   if (!coarse_inverse(ctx->lv[0], ctx->hostB[0], general, inv)) {
@@ -885,7 +923,7 @@ hdgmg_status build_transfers(hdgmg_ctx* ctx) {
   }
   ctx->n0 = 2 * ctx->lv[0].nint;
   TRY(upload(ctx, &ctx->coarse_inv, inv));
-  if (ctx->opts.vcycle_precision == 1) TRY(upload_f32(ctx, &ctx->coarse_inv32, inv));
+  if (vc_f32(ctx)) TRY(upload_f32(ctx, &ctx->coarse_inv32, inv));
   return HDGMG_OK;
 }
 
@@ -969,7 +1007,7 @@ hdgmg_status level_records(hdgmg_ctx* ctx, int l, int max_items, LevelRecords& R
   R.nit = nit;
   R.meta.assign((size_t)8 * nit, 0u);
   // value groups: pairs for FP64 storage, quads for FP32 (16-byte loads)
-  const int G = ctx->opts.vcycle_precision == 1 ? 4 : 2;
+  const int G = vc_f32(ctx) ? 4 : 2;
   const int nvg = (COARSE_NNZ + G - 1) / G, nag = (std::max(nsm, 1) + G - 1) / G;
   R.val.assign((size_t)nvg * G * nit, 0.0);
   R.ainv.assign((size_t)nag * G * nit, 0.0);
@@ -996,7 +1034,7 @@ hdgmg_status level_records(hdgmg_ctx* ctx, int l, int max_items, LevelRecords& R
 
 // Upload a float or double copy of host values (the V-cycle's storage).
 hdgmg_status upload_vals(hdgmg_ctx* ctx, const std::vector<double>& h, const void** out) {
-  if (ctx->opts.vcycle_precision == 1) {
+  if (vc_f32(ctx)) {
     float* tf;
     TRY(upload_f32(ctx, &tf, h));
     *out = tf;
@@ -1066,7 +1104,7 @@ hdgmg_status build_coarse(hdgmg_ctx* ctx) {
     TRY(upload_vals(ctx, R.rw_val, &C.rw_val));
     TRY(upload(ctx, &ti, R.rw_col));
     C.rw_col = ti;
-    const bool f32 = ctx->opts.vcycle_precision == 1;
+    const bool f32 = vc_f32(ctx);
     const DevTransfer& T = ctx->tr[l];
     C.R_w = T.Rw;
     C.R_ci = T.Re_ci;
@@ -1078,7 +1116,7 @@ hdgmg_status build_coarse(hdgmg_ctx* ctx) {
   // Record parts that stay in LDS for the whole kernel, coarsest levels
   // first (they have the most sweeps): residual rows before inverse rows.
   {
-    const bool f32 = ctx->opts.vcycle_precision == 1;
+    const bool f32 = vc_f32(ctx);
     const size_t G = f32 ? 4 : 2;
     const size_t cap = COARSE_LDS_BYTES - coarse_cycle_static_lds() - 256;
     size_t bytes = ((size_t)off * sizeof(double) + 15) / 16 * 16;
@@ -1128,7 +1166,7 @@ hdgmg_status build_record_levels(hdgmg_ctx* ctx) {
     D.rcb = R.cb;
     D.rnit = R.nit;
     D.rnsm = R.nsm;
-    const double ws = ctx->opts.vcycle_precision == 1 ? 4.0 : 8.0;
+    const double ws = vc_f32(ctx) ? 4.0 : 8.0;
     D.rec_bytes.assign(L.ncol, 0.0);
     for (int c = 0; c < L.ncol; ++c) {
       const double items = R.bitem[R.cb[c + 1]] - R.bitem[R.cb[c]];
@@ -1201,7 +1239,7 @@ hdgmg_status assemble_levels(hdgmg_ctx* ctx) {
               nullptr));
   TRY(patch_inverses(ctx, ctx->K));
   TRY(pack_fast(ctx, ctx->K));
-  TRY(make_f32(ctx, ctx->K));
+  TRY(make_f32(ctx, ctx->K, true));
   ctx->hostB.assign(ctx->J, {});
   std::vector<std::vector<double>> nu;
   level_viscosities(ctx->lv, ctx->nu_fine, nu);
@@ -1304,7 +1342,7 @@ hdgmg_status hdgmg_setup(const hdgmg_mesh* mesh, int k, double beta, const doubl
   if (ctx->opts.m_relax < 0 || ctx->opts.m_smooth < 1 || ctx->opts.cycle < 1 || ctx->opts.cycle > 2 ||
       ctx->opts.vcycle_growth < 1 || ctx->opts.max_it < 1 || ctx->opts.uzawa_max < 1 ||
       ctx->opts.uzawa_max > HDGMG_MAX_UZAWA || !(ctx->opts.rtol >= 0) || !(ctx->opts.atol >= 0) ||
-      ctx->opts.vcycle_precision < 0 || ctx->opts.vcycle_precision > 1 || ctx->opts.oseen < 0 ||
+      ctx->opts.vcycle_precision < 0 || ctx->opts.vcycle_precision > 2 || ctx->opts.oseen < 0 ||
       ctx->opts.oseen > 1 || ctx->opts.restart < 1 || ctx->opts.restart > 64) {
     g_setup_error = "invalid options";
     delete ctx;
@@ -1433,7 +1471,10 @@ hdgmg_status hdgmg_setup(const hdgmg_mesh* mesh, int k, double beta, const doubl
     need = std::max(need, ((size_t)D->max_ns * D->max_ns + D->max_ns) * D->npatch * sizeof(double));
   for (auto& D : ctx->cr)
     need = std::max(need, ((size_t)D.max_ns * D.max_ns + D.max_ns) * D.npatch * sizeof(double));
-  size_t el = (size_t)element_ws_size(k) * sizeof(double) * std::min<long>(LF.nc, 16384);
+  // the local solves run a thread per cell, so a launch should cover as many
+  // cells as the workspace allows (all of them up to 6 GiB)
+  const size_t per_cell = (size_t)element_ws_size(k) * sizeof(double);
+  size_t el = per_cell * std::min<size_t>(LF.nc, std::max<size_t>(1, (6ull << 30) / per_cell));
   need = std::max(need, el);
   ctx->ws_bytes = need;
   double* ws = nullptr;
@@ -1503,7 +1544,7 @@ hdgmg_status hdgmg_assemble(hdgmg_ctx* ctx) {
       visits *= o.cycle;
       m_l *= o.vcycle_growth;
     }
-    v += visits * (double)ctx->n0 * ctx->n0 * (o.vcycle_precision == 1 ? 4.0 : 8.0);
+    v += visits * (double)ctx->n0 * ctx->n0 * (o.vcycle_precision >= 1 ? 4.0 : 8.0);
     ctx->vcycle_bytes = v;
   }
   ctx->assembled = true;
