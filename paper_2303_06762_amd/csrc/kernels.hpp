@@ -48,6 +48,10 @@ struct ElemLevel {
 };
 
 void launch_condense(hipStream_t st, const ElemLevel& E, int c0, int nbatch, double* ws, double* S, int* status);
+// The same condensation with a wavefront per cell and the cell's matrices in
+// LDS (condense.hip), all E.nc cells in one launch, for 1 <= k <= 4.
+bool condense_wave_supported(int k);
+void launch_condense_wave(hipStream_t st, const ElemLevel& E, double* S, int* status);
 // gK = g_K(f) - S_K lambda_K^b (boundary lift when E.bdl is set)
 void launch_load(hipStream_t st, const ElemLevel& E, int c0, int nbatch, const double* f, double* ws, double* gK,
                  int* status);

@@ -1212,6 +1212,11 @@ hdgmg_status batched(hdgmg_ctx* ctx, DevLevel& D, const ElemLevel& E, int mode, 
   long per = element_ws_size(E.Q.k);
   long batch = std::max<long>(1, std::min<long>(nc, (long)(ctx->ws_bytes / (per * sizeof(double)))));
   HIPC(hipMemsetAsync(ctx->status, 0, sizeof(int), ctx->st));
+  if (mode == EL_CONDENSE && condense_wave_supported(E.Q.k)) {
+    launch_condense_wave(ctx->st, E, out1, ctx->status);
+    HIPC(hipGetLastError());
+    return check_status(ctx, "condensation");
+  }
   for (long c0 = 0; c0 < nc; c0 += batch) {
     int nb = (int)std::min<long>(batch, nc - c0);
     if (mode == EL_CONDENSE)
