@@ -302,43 +302,43 @@ __global__ void __launch_bounds__(CT) k_coarse_cycle(const CoarseLevel* __restri
 }
 
 // One colour phase of record-based block Gauss-Seidel: a workgroup per
-// patch-aligned batch, a thread per patch row.  Patches of one colour share
-// no cell, so the rows a batch reads are never written by another batch of
-// the same launch.
+// patch-aligned batch of exactly GS_REC_THREADS item slots (batches padded
+// with items whose row marker is 0xffff), a thread per patch row, so that a
+// thread's item index needs no lookup.  Patches of one colour share no cell,
+// so the rows a batch reads are never written by another batch of the same
+// launch.
 template <int NS, typename TS>
 __global__ void __launch_bounds__(GS_REC_THREADS)
     k_gs_records(const uint4* __restrict__ meta, const TS* __restrict__ val, const TS* __restrict__ ainv, int nit,
-                 int nsm, const int* __restrict__ bitem, int b0, double* __restrict__ u,
-                 const double* __restrict__ g) {
+                 int nsm, int b0, double* __restrict__ u, const double* __restrict__ g) {
   __shared__ double res[GS_REC_THREADS + NS];
   const int tid = threadIdx.x;
-  const int b = b0 + blockIdx.x;
-  const int t = bitem[b] + tid;
-  const bool on = t < bitem[b + 1];
+  const int t = (b0 + blockIdx.x) * GS_REC_THREADS + tid;
   if (tid < NS) res[GS_REC_THREADS + tid] = 0.0;
-  unsigned k = 0;
-  double r = 0.0;
   using GT = Grp<TS>;
   using V = typename GT::T;
   constexpr int G = GT::G;
-  if (on) {
-    const uint4 m0 = meta[t], m1 = meta[nit + t];
-    const unsigned cols[COARSE_NNZ / 2] = {m0.y, m0.z, m0.w, m1.x, m1.y};
-    TS vals[((COARSE_NNZ + G - 1) / G) * G];
+  // every load of the item is independent of the others: issue them together
+  const uint4 m0 = meta[t], m1 = meta[nit + t];
+  V av[NS / G];
 #pragma unroll
-    for (int e = 0; e < (COARSE_NNZ + G - 1) / G; ++e) {
-      const V v = ((const V*)val)[e * nit + t];
+  for (int j = 0; j < NS / G; ++j) av[j] = j * G < nsm ? ((const V*)ainv)[j * nit + t] : (V)(TS)0;
+  TS vals[((COARSE_NNZ + G - 1) / G) * G];
 #pragma unroll
-      for (int i = 0; i < G; ++i) vals[e * G + i] = GT::get(v, i);
-    }
-    k = m0.x;
-    r = g[k & 0xffff];
+  for (int e = 0; e < (COARSE_NNZ + G - 1) / G; ++e) {
+    const V v = ((const V*)val)[e * nit + t];
 #pragma unroll
-    for (int q = 0; q < COARSE_NNZ / 2; ++q) {
-      const unsigned c = cols[q];
-      r -= (double)vals[2 * q] * u[c & 0xffff];
-      r -= (double)vals[2 * q + 1] * u[c >> 16];
-    }
+    for (int i = 0; i < G; ++i) vals[e * G + i] = GT::get(v, i);
+  }
+  const unsigned k = m0.x;
+  const bool on = (k >> 16) != 0xffffu;
+  const unsigned cols[COARSE_NNZ / 2] = {m0.y, m0.z, m0.w, m1.x, m1.y};
+  double r = g[k & 0xffff];
+#pragma unroll
+  for (int q = 0; q < COARSE_NNZ / 2; ++q) {
+    const unsigned c = cols[q];
+    r -= (double)vals[2 * q] * u[c & 0xffff];
+    r -= (double)vals[2 * q + 1] * u[c >> 16];
   }
   res[tid] = on ? r : 0.0;
   __syncthreads();
@@ -346,39 +346,37 @@ __global__ void __launch_bounds__(GS_REC_THREADS)
     const int base = tid - (int)(k >> 16);
     double d = 0.0;
 #pragma unroll
-    for (int j = 0; j < NS / G; ++j) {
-      const V v = j * G < nsm ? ((const V*)ainv)[j * nit + t] : (V)(TS)0;
+    for (int j = 0; j < NS / G; ++j)
 #pragma unroll
-      for (int i = 0; i < G; ++i) d += (double)GT::get(v, i) * res[base + j * G + i];
-    }
+      for (int i = 0; i < G; ++i) d += (double)GT::get(av[j], i) * res[base + j * G + i];
     u[k & 0xffff] += d;
   }
 }
 
 template <typename TS>
-void gs_records_t(hipStream_t st, const uint4* meta, const TS* val, const TS* ainv, int nit, int nsm,
-                  const int* bitem, int b0, int nb, double* u, const double* g) {
+void gs_records_t(hipStream_t st, const uint4* meta, const TS* val, const TS* ainv, int nit, int nsm, int b0,
+                  int nb, double* u, const double* g) {
   if (nsm <= 12)
-    hipLaunchKernelGGL((k_gs_records<12, TS>), dim3(nb), dim3(GS_REC_THREADS), 0, st, meta, val, ainv, nit, nsm,
-                       bitem, b0, u, g);
+    hipLaunchKernelGGL((k_gs_records<12, TS>), dim3(nb), dim3(GS_REC_THREADS), 0, st, meta, val, ainv, nit, nsm, b0,
+                       u, g);
   else if (nsm <= 16)
-    hipLaunchKernelGGL((k_gs_records<16, TS>), dim3(nb), dim3(GS_REC_THREADS), 0, st, meta, val, ainv, nit, nsm,
-                       bitem, b0, u, g);
+    hipLaunchKernelGGL((k_gs_records<16, TS>), dim3(nb), dim3(GS_REC_THREADS), 0, st, meta, val, ainv, nit, nsm, b0,
+                       u, g);
   else
-    hipLaunchKernelGGL((k_gs_records<32, TS>), dim3(nb), dim3(GS_REC_THREADS), 0, st, meta, val, ainv, nit, nsm,
-                       bitem, b0, u, g);
+    hipLaunchKernelGGL((k_gs_records<32, TS>), dim3(nb), dim3(GS_REC_THREADS), 0, st, meta, val, ainv, nit, nsm, b0,
+                       u, g);
 }
 
 }  // namespace
 
 void launch_gs_records(hipStream_t st, const unsigned* meta, const void* val, const void* ainv, int nit, int nsm,
-                       const int* bitem, int b0, int nb, double* u, const double* g, int f32) {
+                       int b0, int nb, double* u, const double* g, int f32) {
   if (nb <= 0) return;
   const uint4* m = (const uint4*)meta;
   if (f32)
-    gs_records_t<float>(st, m, (const float*)val, (const float*)ainv, nit, nsm, bitem, b0, nb, u, g);
+    gs_records_t<float>(st, m, (const float*)val, (const float*)ainv, nit, nsm, b0, nb, u, g);
   else
-    gs_records_t<double>(st, m, (const double*)val, (const double*)ainv, nit, nsm, bitem, b0, nb, u, g);
+    gs_records_t<double>(st, m, (const double*)val, (const double*)ainv, nit, nsm, b0, nb, u, g);
 }
 
 template <typename TS>

@@ -54,11 +54,12 @@ constexpr int GS_REC_THREADS = 256;
 
 // One colour phase of block Gauss-Seidel on a launched lowest-order level
 // from its patch-row records (the same structure-of-arrays record layout as
-// CoarseLevel: meta, val, ainv over nit items; batches [b0, b0 + nb) of
-// bitem, patch-aligned, at most GS_REC_THREADS items): u += A_ss^-1 (g - A u)_s
-// for every patch of the colour.  f32: val and ainv are float, else double.
+// CoarseLevel: meta, val, ainv over nit items), batches [b0, b0 + nb) of
+// exactly GS_REC_THREADS item slots each (patch-aligned, padded with items
+// whose row marker is 0xffff): u += A_ss^-1 (g - A u)_s for every patch of
+// the colour.  f32: val and ainv are float, else double.
 void launch_gs_records(hipStream_t st, const unsigned* meta, const void* val, const void* ainv, int nit, int nsm,
-                       const int* bitem, int b0, int nb, double* u, const double* g, int f32);
+                       int b0, int nb, double* u, const double* g, int f32);
 
 // u_top <- MG_h(top, g_top, u_top, m_top, q) with m(l-1) = growth m(l) on
 // levels 0..top (top <= the levels described by Ls); level 0 is solved with

@@ -56,7 +56,6 @@ struct DevLevel {
   bool rec = false;
   unsigned* rk = nullptr;  // [2][nit][4] meta words
   const void *rv = nullptr, *ra = nullptr;
-  int* rbitem = nullptr;
   std::vector<int> rcb;
   int rnit = 0, rnsm = 0;
   std::vector<double> rec_bytes;
@@ -553,7 +552,7 @@ void sweep(hdgmg_ctx* ctx, DevLevel& D, double* x, const double* b, bool forward
       kt_end(ctx, level < 0 ? 0 : 2, t, D.bytes_relax_vc[c]);
     } else if (D.rec) {
       int t = kt_begin(ctx, 2);
-      launch_gs_records(ctx->st, D.rk, D.rv, D.ra, D.rnit, D.rnsm, D.rbitem, D.rcb[c], D.rcb[c + 1] - D.rcb[c],
+      launch_gs_records(ctx->st, D.rk, D.rv, D.ra, D.rnit, D.rnsm, D.rcb[c], D.rcb[c + 1] - D.rcb[c],
                         x, b, D.f32 ? 1 : 0);
       kt_end(ctx, 2, t, phase_bytes(ctx, D, level, c));
     } else {
@@ -947,7 +946,10 @@ struct LevelRecords {
   std::vector<double> rw_val;
 };
 
-hdgmg_status level_records(hdgmg_ctx* ctx, int l, int max_items, LevelRecords& R) {
+// pad: every batch fills exactly max_items item slots (padding items carry
+// the row marker 0xffff and zero values), so that batch b starts at item
+// b * max_items.
+hdgmg_status level_records(hdgmg_ctx* ctx, int l, int max_items, LevelRecords& R, bool pad = false) {
   const Level& L = ctx->lv[l];
   const int n = 2 * L.nint;
   R = LevelRecords();
@@ -993,14 +995,28 @@ hdgmg_status level_records(hdgmg_ctx* ctx, int l, int max_items, LevelRecords& R
         ctx->err = "singular patch block on a lowest-order level";
         return HDGMG_ENONFINITE;
       }
-      if ((int)idof.size() - R.bitem.back() + ns > max_items) R.bitem.push_back((int)idof.size());
+      if ((int)idof.size() - R.bitem.back() + ns > max_items) {
+        while (pad && (int)idof.size() - R.bitem.back() < max_items) {
+          idof.push_back(-1);
+          iloc.push_back(0xffff);
+          for (int j = 0; j < nsm; ++j) irow.push_back(0.0);
+        }
+        R.bitem.push_back((int)idof.size());
+      }
       for (int i = 0; i < ns; ++i) {
         idof.push_back(dofs[i]);
         iloc.push_back(i);
         for (int j = 0; j < nsm; ++j) irow.push_back(j < ns ? inv[(size_t)j * ns + i] : 0.0);  // row i
       }
     }
-    if ((int)idof.size() > R.bitem.back()) R.bitem.push_back((int)idof.size());
+    if ((int)idof.size() > R.bitem.back()) {
+      while (pad && (int)idof.size() - R.bitem.back() < max_items) {
+        idof.push_back(-1);
+        iloc.push_back(0xffff);
+        for (int j = 0; j < nsm; ++j) irow.push_back(0.0);
+      }
+      R.bitem.push_back((int)idof.size());
+    }
     R.cb.push_back((int)R.bitem.size() - 1);
   }
   const int nit = (int)idof.size();
@@ -1012,6 +1028,10 @@ hdgmg_status level_records(hdgmg_ctx* ctx, int l, int max_items, LevelRecords& R
   R.val.assign((size_t)nvg * G * nit, 0.0);
   R.ainv.assign((size_t)nag * G * nit, 0.0);
   for (int t = 0; t < nit; ++t) {
+    if (idof[t] < 0) {  // padding: row marker 0xffff, unknown 0, zero values
+      R.meta[(size_t)t * 4] = 0xffffu << 16;
+      continue;
+    }
     // meta: (key, cols 0-2) and (cols 3-4, 0, 0), two 16-byte words per item
     R.meta[(size_t)t * 4] = (unsigned)idof[t] | ((unsigned)iloc[t] << 16);
     // values in groups of G: entry e of item t at [((e / G) * nit + t) * G + e % G]
@@ -1158,18 +1178,18 @@ hdgmg_status build_record_levels(hdgmg_ctx* ctx) {
     const Level& L = ctx->lv[l];
     if (D.fast || 2 * L.nint > 65535 || 2 * L.max_patch_facets > 32) continue;
     LevelRecords R;
-    TRY(level_records(ctx, l, GS_REC_THREADS, R));
+    TRY(level_records(ctx, l, GS_REC_THREADS, R, true));
     TRY(upload(ctx, &D.rk, R.meta));
     TRY(upload_vals(ctx, R.val, &D.rv));
     TRY(upload_vals(ctx, R.ainv, &D.ra));
-    TRY(upload(ctx, &D.rbitem, R.bitem));
     D.rcb = R.cb;
     D.rnit = R.nit;
     D.rnsm = R.nsm;
     const double ws = vc_f32(ctx) ? 4.0 : 8.0;
     D.rec_bytes.assign(L.ncol, 0.0);
     for (int c = 0; c < L.ncol; ++c) {
-      const double items = R.bitem[R.cb[c + 1]] - R.bitem[R.cb[c]];
+      double items = 0.0;  // patch rows, padding excluded
+      for (int t = R.bitem[R.cb[c]]; t < R.bitem[R.cb[c + 1]]; ++t) items += (R.meta[(size_t)t * 4] >> 16) != 0xffffu;
       D.rec_bytes[c] = items * (4.0 + 4.0 * (COARSE_NNZ / 2) + ws * (COARSE_NNZ + R.nsm) + 8.0 * (COARSE_NNZ + 2));
     }
     D.rec = true;
