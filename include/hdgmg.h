@@ -93,7 +93,11 @@ typedef struct {
                               kernel (0: every level launch by launch)     */
   int stream_dofs;         /* levels with at least this many unknowns (and
                               vertex patches of at most 6 facets) use the
-                              streaming cell-apply / patch-relax kernels   */
+                              streaming cell-apply / patch-relax kernels;
+                              lowest-order levels with at most 65535
+                              interior facets smooth with the patch-row
+                              record kernel instead, unless stream_dofs
+                              is 0 (streaming on every level)             */
   int vcycle_precision;    /* storage of every operator the preconditioner
                               reads: 0 FP64, 1 FP32, 2 FP32 with the
                               order-k level's streaming cell blocks (k <= 2,

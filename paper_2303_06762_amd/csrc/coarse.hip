@@ -33,11 +33,12 @@ __device__ inline const __attribute__((address_space(1))) T* gmem(const T* p) {
   return (const __attribute__((address_space(1))) T*)p;
 }
 
-// The record of one patch row: its unknown and row, residual row, inverse row.
+// The record of one patch row: its unknown and row, the facets of its
+// residual row (two 16-bit indices per word), residual row, inverse row.
 template <int NS, typename TS>
 struct Rec {
   unsigned key;
-  unsigned col[COARSE_NNZ / 2];
+  unsigned fac[3];
   TS val[COARSE_NNZ];
   TS ai[NS];
 };
@@ -70,22 +71,15 @@ __device__ inline void load_rec(const CoarseLevel& L, const char* lds, int t, Re
   using V = typename GT::T;
   constexpr int G = GT::G;
   const int nit = L.nitems;
-  u32x4 m0, m1;
-  if (L.lds_meta >= 0) {
-    const u32x4* meta = (const u32x4*)(lds + L.lds_meta);
-    m0 = meta[t];
-    m1 = meta[nit + t];
-  } else {
-    const auto meta = gmem((const u32x4*)L.it_meta);
-    m0 = meta[t];
-    m1 = meta[nit + t];
-  }
+  u32x4 m0;
+  if (L.lds_meta >= 0)
+    m0 = ((const u32x4*)(lds + L.lds_meta))[t];
+  else
+    m0 = gmem((const u32x4*)L.it_meta)[t];
   r.key = m0.x;
-  r.col[0] = m0.y;
-  r.col[1] = m0.z;
-  r.col[2] = m0.w;
-  r.col[3] = m1.x;
-  r.col[4] = m1.y;
+  r.fac[0] = m0.y;
+  r.fac[1] = m0.z;
+  r.fac[2] = m0.w;
   constexpr int NVG = (COARSE_NNZ + G - 1) / G;
   V vg[NVG];
   if (L.lds_val >= 0) {
@@ -165,13 +159,13 @@ __device__ void smooth(const CoarseLevel& Ld, const char* lds, const int* bitem,
     const bool on = t < bitem[b + 1];
     Rec<NS, TS> cur;
     if (on) load_rec<NS, TS>(L, lds, t, cur);
-    const int dof = cur.key & 0xffff, loc = cur.key >> 16;
+    const int dof = cur.key & REC_DOF_MASK, loc = cur.key >> REC_LOC_SHIFT;
     if (on) {
       double r = g[dof];
 #pragma unroll
-      for (int k = 0; k < COARSE_NNZ / 2; ++k) {
-        r -= (double)cur.val[2 * k] * u[cur.col[k] & 0xffff];
-        r -= (double)cur.val[2 * k + 1] * u[cur.col[k] >> 16];
+      for (int q = 0; q < COARSE_NNZ / 2; ++q) {
+        const int F = (cur.fac[q / 2] >> (16 * (q % 2))) & 0xffff;
+        r -= (double)cur.val[2 * q] * u[2 * F] + (double)cur.val[2 * q + 1] * u[2 * F + 1];
       }
       res[tid] = r;
     }
@@ -207,7 +201,7 @@ __global__ void __launch_bounds__(CT) k_coarse_cycle(const CoarseLevel* __restri
     if (tid < L.nbatch) sbwd[l][tid] = gmem(L.bseq_bwd)[tid];
     // record parts resident in LDS for the whole kernel (16-byte words)
     const int nit = L.nitems;
-    if (L.lds_meta >= 0) copy_to_lds((char*)smem + L.lds_meta, L.it_meta, 2 * nit);
+    if (L.lds_meta >= 0) copy_to_lds((char*)smem + L.lds_meta, L.it_meta, nit);
     if (L.lds_val >= 0) copy_to_lds((char*)smem + L.lds_val, L.it_val, (COARSE_NNZ + G - 1) / G * nit);
     if (L.lds_ainv >= 0) copy_to_lds((char*)smem + L.lds_ainv, L.it_ainv, (L.ns_max + G - 1) / G * nit);
   }
@@ -303,7 +297,7 @@ __global__ void __launch_bounds__(CT) k_coarse_cycle(const CoarseLevel* __restri
 
 // One colour phase of record-based block Gauss-Seidel: a workgroup per
 // patch-aligned batch of exactly GS_REC_THREADS item slots (batches padded
-// with items whose row marker is 0xffff), a thread per patch row, so that a
+// with items whose row marker is REC_PAD), a thread per patch row, so that a
 // thread's item index needs no lookup.  Patches of one colour share no cell,
 // so the rows a batch reads are never written by another batch of the same
 // launch.
@@ -319,7 +313,7 @@ __global__ void __launch_bounds__(GS_REC_THREADS)
   using V = typename GT::T;
   constexpr int G = GT::G;
   // every load of the item is independent of the others: issue them together
-  const uint4 m0 = meta[t], m1 = meta[nit + t];
+  const uint4 m0 = meta[t];
   V av[NS / G];
 #pragma unroll
   for (int j = 0; j < NS / G; ++j) av[j] = j * G < nsm ? ((const V*)ainv)[j * nit + t] : (V)(TS)0;
@@ -331,25 +325,25 @@ __global__ void __launch_bounds__(GS_REC_THREADS)
     for (int i = 0; i < G; ++i) vals[e * G + i] = GT::get(v, i);
   }
   const unsigned k = m0.x;
-  const bool on = (k >> 16) != 0xffffu;
-  const unsigned cols[COARSE_NNZ / 2] = {m0.y, m0.z, m0.w, m1.x, m1.y};
-  double r = g[k & 0xffff];
+  const bool on = (k >> REC_LOC_SHIFT) != REC_PAD;
+  const unsigned fw[3] = {m0.y, m0.z, m0.w};
+  double r = g[k & REC_DOF_MASK];
 #pragma unroll
   for (int q = 0; q < COARSE_NNZ / 2; ++q) {
-    const unsigned c = cols[q];
-    r -= (double)vals[2 * q] * u[c & 0xffff];
-    r -= (double)vals[2 * q + 1] * u[c >> 16];
+    const int F = (fw[q / 2] >> (16 * (q % 2))) & 0xffff;
+    const double2 uf = *(const double2*)(u + 2 * F);
+    r -= (double)vals[2 * q] * uf.x + (double)vals[2 * q + 1] * uf.y;
   }
   res[tid] = on ? r : 0.0;
   __syncthreads();
   if (on) {
-    const int base = tid - (int)(k >> 16);
+    const int base = tid - (int)(k >> REC_LOC_SHIFT);
     double d = 0.0;
 #pragma unroll
     for (int j = 0; j < NS / G; ++j)
 #pragma unroll
       for (int i = 0; i < G; ++i) d += (double)GT::get(av[j], i) * res[base + j * G + i];
-    u[k & 0xffff] += d;
+    u[k & REC_DOF_MASK] += d;
   }
 }
 

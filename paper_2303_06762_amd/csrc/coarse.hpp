@@ -7,8 +7,14 @@ namespace hdgmg {
 constexpr int COARSE_THREADS = 1024;
 constexpr int COARSE_MAX_LEVELS = 8;
 // A lowest-order unknown couples with the 10 unknowns of the facets of its
-// two cells (fewer next to the boundary): rows are padded to 10 entries.
+// two cells (fewer next to the boundary): rows are padded to 10 entries,
+// both components of 5 facets.
 constexpr int COARSE_NNZ = 10;
+// Patch-row record key: the unknown in bits 0-17, the row inside its patch
+// in bits 18-31; padding items carry the row REC_PAD.
+constexpr int REC_LOC_SHIFT = 18;
+constexpr unsigned REC_DOF_MASK = (1u << REC_LOC_SHIFT) - 1;
+constexpr unsigned REC_PAD = 0x3fffu;
 // Level vectors u, g, r of the coarse levels live in LDS: at most this many
 // doubles in total.
 constexpr int COARSE_LDS_DOUBLES = 6144;
@@ -32,11 +38,11 @@ struct CoarseLevel {
   const int* bitem;           // [nbatch+1] item range of each batch
                               // (<= COARSE_THREADS items, patch-aligned)
   const int* bseq_bwd;        // [nbatch] batches in reverse colour order
-  const uint4* it_meta;       // [2][nitems]: (key, cols01, cols23, cols45),
-                              // (cols67, cols89, 0, 0); key = unknown |
-                              // (row inside its patch) << 16, columns two
-                              // 16-bit indices per word
-  const void* it_val;         // [COARSE_NNZ/2][nitems][2] residual row values (pairs)
+  const uint4* it_meta;       // [nitems]: (key, F0 | F1 << 16, F2 | F3 << 16,
+                              // F4): the residual row's 5 facets (16-bit),
+                              // columns 2F and 2F + 1 each
+  const void* it_val;         // residual row values (facet q, component c) at
+                              // 2q + c, in 16-byte groups over items
   const void* it_ainv;        // [ns_max/2][nitems][2] row of the patch inverse (pairs)
   const int* rw_col;          // [COARSE_NNZ][n] rows of A for the residual
   const void* rw_val;
@@ -56,7 +62,7 @@ constexpr int GS_REC_THREADS = 256;
 // from its patch-row records (the same structure-of-arrays record layout as
 // CoarseLevel: meta, val, ainv over nit items), batches [b0, b0 + nb) of
 // exactly GS_REC_THREADS item slots each (patch-aligned, padded with items
-// whose row marker is 0xffff): u += A_ss^-1 (g - A u)_s for every patch of
+// whose row marker is REC_PAD): u += A_ss^-1 (g - A u)_s for every patch of
 // the colour.  f32: val and ainv are float, else double.
 void launch_gs_records(hipStream_t st, const unsigned* meta, const void* val, const void* ainv, int nit, int nsm,
                        int b0, int nb, double* u, const double* g, int f32);

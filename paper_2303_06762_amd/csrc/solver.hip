@@ -514,8 +514,8 @@ hdgmg_status upload_f32(hdgmg_ctx* ctx, float** p, const std::vector<T>& h) {
 // Algorithmic bytes of Gauss-Seidel colour phase c of a level (level < 0:
 // the order-k level) in the storage the V-cycle reads.
 double phase_bytes(const hdgmg_ctx* ctx, const DevLevel& D, int level, int c) {
-  if (D.fast) return D.bytes_cell_vc + D.bytes_relax_vc[c];
   if (D.rec) return D.rec_bytes[c];
+  if (D.fast) return D.bytes_cell_vc + D.bytes_relax_vc[c];
   const double scale = D.f32 ? 0.5 : 1.0;  // operator words dominate the phase bytes
   return scale * (level < 0 ? ctx->relax_bytes[c] : ctx->smooth_bytes[level][c]);
 }
@@ -527,7 +527,12 @@ void sweep(hdgmg_ctx* ctx, DevLevel& D, double* x, const double* b, bool forward
   const int nc = (int)D.colour_ptr.size() - 1;
   for (int i = 0; i < nc; ++i) {
     int c = forward ? i : nc - 1 - i;
-    if (D.fast) {
+    if (D.rec) {
+      int t = kt_begin(ctx, 2);
+      launch_gs_records(ctx->st, D.rk, D.rv, D.ra, D.rnit, D.rnsm, D.rcb[c], D.rcb[c + 1] - D.rcb[c], x, b,
+                        D.f32 ? 1 : 0);
+      kt_end(ctx, 2, t, phase_bytes(ctx, D, level, c));
+    } else if (D.fast) {
       // colour phase = cell apply (all cells) + patch relaxation (colour c)
       const bool skip = x_zero && i == 0;
       int t;
@@ -550,11 +555,6 @@ void sweep(hdgmg_ctx* ctx, DevLevel& D, double* x, const double* b, bool forward
       else
         launch_patch_relax<double>(ctx->st, 2 * D.m, D.npc[c], D.pfc[c], D.Ppc[c], b, yF, x, D.pfull);
       kt_end(ctx, level < 0 ? 0 : 2, t, D.bytes_relax_vc[c]);
-    } else if (D.rec) {
-      int t = kt_begin(ctx, 2);
-      launch_gs_records(ctx->st, D.rk, D.rv, D.ra, D.rnit, D.rnsm, D.rcb[c], D.rcb[c + 1] - D.rcb[c],
-                        x, b, D.f32 ? 1 : 0);
-      kt_end(ctx, 2, t, phase_bytes(ctx, D, level, c));
     } else {
       const int cls = level < 0 ? 0 : 2;
       int t = kt_begin(ctx, cls);
@@ -947,15 +947,15 @@ struct LevelRecords {
 };
 
 // pad: every batch fills exactly max_items item slots (padding items carry
-// the row marker 0xffff and zero values), so that batch b starts at item
+// the row marker REC_PAD and zero values), so that batch b starts at item
 // b * max_items.
 hdgmg_status level_records(hdgmg_ctx* ctx, int l, int max_items, LevelRecords& R, bool pad = false) {
   const Level& L = ctx->lv[l];
   const int n = 2 * L.nint;
   R = LevelRecords();
   R.n = n;
-  if (n > 65535) {
-    ctx->err = "level too large for 16-bit record indices";
+  if (L.nint > 65535) {
+    ctx->err = "level too large for 16-bit record facet indices";
     return HDGMG_EMESH;
   }
   CSR A;
@@ -998,7 +998,7 @@ hdgmg_status level_records(hdgmg_ctx* ctx, int l, int max_items, LevelRecords& R
       if ((int)idof.size() - R.bitem.back() + ns > max_items) {
         while (pad && (int)idof.size() - R.bitem.back() < max_items) {
           idof.push_back(-1);
-          iloc.push_back(0xffff);
+          iloc.push_back((int)REC_PAD);
           for (int j = 0; j < nsm; ++j) irow.push_back(0.0);
         }
         R.bitem.push_back((int)idof.size());
@@ -1012,7 +1012,7 @@ hdgmg_status level_records(hdgmg_ctx* ctx, int l, int max_items, LevelRecords& R
     if ((int)idof.size() > R.bitem.back()) {
       while (pad && (int)idof.size() - R.bitem.back() < max_items) {
         idof.push_back(-1);
-        iloc.push_back(0xffff);
+        iloc.push_back((int)REC_PAD);
         for (int j = 0; j < nsm; ++j) irow.push_back(0.0);
       }
       R.bitem.push_back((int)idof.size());
@@ -1021,29 +1021,32 @@ hdgmg_status level_records(hdgmg_ctx* ctx, int l, int max_items, LevelRecords& R
   }
   const int nit = (int)idof.size();
   R.nit = nit;
-  R.meta.assign((size_t)8 * nit, 0u);
+  R.meta.assign((size_t)4 * nit, 0u);
   // value groups: pairs for FP64 storage, quads for FP32 (16-byte loads)
   const int G = vc_f32(ctx) ? 4 : 2;
   const int nvg = (COARSE_NNZ + G - 1) / G, nag = (std::max(nsm, 1) + G - 1) / G;
   R.val.assign((size_t)nvg * G * nit, 0.0);
   R.ainv.assign((size_t)nag * G * nit, 0.0);
   for (int t = 0; t < nit; ++t) {
-    if (idof[t] < 0) {  // padding: row marker 0xffff, unknown 0, zero values
-      R.meta[(size_t)t * 4] = 0xffffu << 16;
+    if (idof[t] < 0) {  // padding: row marker REC_PAD, unknown 0, zero values
+      R.meta[(size_t)t * 4] = REC_PAD << REC_LOC_SHIFT;
       continue;
     }
-    // meta: (key, cols 0-2) and (cols 3-4, 0, 0), two 16-byte words per item
-    R.meta[(size_t)t * 4] = (unsigned)idof[t] | ((unsigned)iloc[t] << 16);
+    // meta (key, F0 | F1 << 16, F2 | F3 << 16, F4): the row's columns come in
+    // facet pairs (2F, 2F + 1), sorted, padded with zero entries
+    R.meta[(size_t)t * 4] = (unsigned)idof[t] | ((unsigned)iloc[t] << REC_LOC_SHIFT);
     // values in groups of G: entry e of item t at [((e / G) * nit + t) * G + e % G]
     for (int k = 0; k < COARSE_NNZ; ++k)
       R.val[((size_t)(k / G) * nit + t) * G + k % G] = R.rw_val[(size_t)k * n + idof[t]];
-    for (int k = 0; k < COARSE_NNZ / 2; ++k) {
-      const unsigned pc = (unsigned)R.rw_col[(size_t)(2 * k) * n + idof[t]] |
-                          ((unsigned)R.rw_col[(size_t)(2 * k + 1) * n + idof[t]] << 16);
-      if (k < 3)
-        R.meta[(size_t)t * 4 + 1 + k] = pc;
-      else
-        R.meta[((size_t)nit + t) * 4 + (k - 3)] = pc;
+    for (int q = 0; q < COARSE_NNZ / 2; ++q) {
+      const int c0 = R.rw_col[(size_t)(2 * q) * n + idof[t]], c1 = R.rw_col[(size_t)(2 * q + 1) * n + idof[t]];
+      const double v0 = R.rw_val[(size_t)(2 * q) * n + idof[t]], v1 = R.rw_val[(size_t)(2 * q + 1) * n + idof[t]];
+      const bool padded = c0 == 0 && c1 == 0 && v0 == 0.0 && v1 == 0.0;
+      if (!padded && (c0 % 2 != 0 || c1 != c0 + 1)) {
+        ctx->err = "lowest-order row whose columns are not facet pairs";
+        return HDGMG_EMESH;
+      }
+      R.meta[(size_t)t * 4 + 1 + q / 2] |= (unsigned)(padded ? 0 : c0 / 2) << (16 * (q % 2));
     }
     for (int j = 0; j < nsm; ++j) R.ainv[((size_t)(j / G) * nit + t) * G + j % G] = irow[(size_t)t * nsm + j];
   }
@@ -1143,7 +1146,7 @@ hdgmg_status build_coarse(hdgmg_ctx* ctx) {
     for (int l = 1; l <= Lc; ++l) {
       CoarseLevel& C = desc[l];
       const size_t nit = C.nitems;
-      const size_t mb = 32 * nit, vb = (COARSE_NNZ + G - 1) / G * 16 * nit;
+      const size_t mb = 16 * nit, vb = (COARSE_NNZ + G - 1) / G * 16 * nit;
       const size_t ab = (std::max(C.ns_max, 1) + G - 1) / G * 16 * nit;
       if (bytes + mb + vb <= cap) {
         C.lds_meta = (int)bytes;
@@ -1176,7 +1179,10 @@ hdgmg_status build_record_levels(hdgmg_ctx* ctx) {
     DevLevel& D = ctx->cr[l];
     D.rec = false;
     const Level& L = ctx->lv[l];
-    if (D.fast || 2 * L.nint > 65535 || 2 * L.max_patch_facets > 32) continue;
+    // records replace the streaming pair (cell apply + patch relaxation) on
+    // levels small enough for 16-bit facet indices; stream_dofs = 0 keeps
+    // the streaming kernels on every level
+    if (L.nint > 65535 || 2 * L.max_patch_facets > 32 || (D.fast && ctx->opts.stream_dofs == 0)) continue;
     LevelRecords R;
     TRY(level_records(ctx, l, GS_REC_THREADS, R, true));
     TRY(upload(ctx, &D.rk, R.meta));
@@ -1189,8 +1195,9 @@ hdgmg_status build_record_levels(hdgmg_ctx* ctx) {
     D.rec_bytes.assign(L.ncol, 0.0);
     for (int c = 0; c < L.ncol; ++c) {
       double items = 0.0;  // patch rows, padding excluded
-      for (int t = R.bitem[R.cb[c]]; t < R.bitem[R.cb[c + 1]]; ++t) items += (R.meta[(size_t)t * 4] >> 16) != 0xffffu;
-      D.rec_bytes[c] = items * (4.0 + 4.0 * (COARSE_NNZ / 2) + ws * (COARSE_NNZ + R.nsm) + 8.0 * (COARSE_NNZ + 2));
+      for (int t = R.bitem[R.cb[c]]; t < R.bitem[R.cb[c + 1]]; ++t)
+        items += (R.meta[(size_t)t * 4] >> REC_LOC_SHIFT) != REC_PAD;
+      D.rec_bytes[c] = items * (16.0 + ws * (COARSE_NNZ + R.nsm) + 8.0 * (COARSE_NNZ + 2));
     }
     D.rec = true;
   }
@@ -1565,7 +1572,7 @@ hdgmg_status hdgmg_assemble(hdgmg_ctx* ctx) {
                           : (double)D.nc * 36 * ws + (D.nc * 6.0 + 2.0 * D.ndof) * 8.0;
       double trn = 2.0 * (ctx->tr[l].nnz * (4.0 + ws) + (ctx->tr[l].nfine + ctx->tr[l].ncoarse) * 8.0);
       const double zero_starts = l == ctx->J - 1 ? 1.0 : visits / o.cycle;
-      v += visits * (2.0 * m_l * sw + res + trn) - (D.fast ? zero_starts * D.bytes_cell_vc : 0.0);
+      v += visits * (2.0 * m_l * sw + res + trn) - (D.fast && !D.rec ? zero_starts * D.bytes_cell_vc : 0.0);
       visits *= o.cycle;
       m_l *= o.vcycle_growth;
     }
