@@ -26,8 +26,6 @@
 // k_patch_relax (x_s += A_ss^-1 (b - y)_s for the colour's patches).
 #include <hip/hip_runtime.h>
 
-#include <type_traits>
-
 #include "fast.hpp"
 
 namespace hdgmg {
@@ -188,51 +186,52 @@ __global__ void __launch_bounds__(256) k_patch_relax(int np, const int* __restri
   if (f >= 0) x[(long)f * M2 + i % M2] += d;
 }
 
-// The same relaxation from the upper triangle of symmetric FP64 inverses.
-// Row i of an inverse is row i of the upper triangle joined with column i:
-// at step t the thread of row i takes column j = (t - i) mod NS, so that
-// entry (min(i, j), max(i, j)) is read for rows i and j of the same patch
-// in the same step and the second read is served by the cache.  A row group
-// is 16 consecutive patches (128 bytes per entry).  Residuals are held in LDS
-// as rs[j][patch] so that a row group reads consecutive words.  The offsets
-// of step t for row i, (e np, j 16), are tabulated in LDS once per
-// workgroup; they are 32-bit: the host keeps np * NS (NS + 1) / 2 below 2^31.
-constexpr int SYM_PB = 16;
-template <int M2>
-__global__ void __launch_bounds__(FAST_NF * M2 * SYM_PB)
-    k_patch_relax_sym(int np, const int* __restrict__ pf, const double* __restrict__ Pp,
-                      const double* __restrict__ b, const double* __restrict__ yF, double* __restrict__ x) {
-  constexpr int NS = FAST_NF * M2, PB = SYM_PB;
-  __shared__ double rs[NS * PB];
-  __shared__ uint2 tab[NS * NS];
-  for (int k = threadIdx.x; k < NS * NS; k += NS * PB) {
-    const int t = k / NS, i = k % NS;
-    int j = t - i;
-    if (j < 0) j += NS;
-    const int a = min(i, j), e = a * NS - a * (a - 1) / 2 + max(i, j) - a;
-    tab[k] = make_uint2((unsigned)e * (unsigned)np, (unsigned)(j * PB));
+// The same relaxation from the upper triangles of symmetric inverses, a
+// wavefront per patch: the patch's triangle (contiguous, PW words) is read
+// once with 16-byte loads by all 64 lanes into LDS, the patch residual goes
+// to LDS, and lane i < NS forms row i of the inverse times the residual from
+// the triangle: entry (i, j) at e(min(i, j), max(i, j)), e(a, b) = a NS -
+// a (a - 1) / 2 + b - a.  Every entry crosses HBM once.  sc: per-patch
+// scale of FP16 triangles, else null.
+template <int M2, typename TS>
+__global__ void __launch_bounds__(64) k_patch_relax_wave(int np, const int* __restrict__ pf, const TS* __restrict__ Pp,
+                                                         const double* __restrict__ b, const double* __restrict__ yF,
+                                                         double* __restrict__ x, const float* __restrict__ sc) {
+  constexpr int NS = FAST_NF * M2;
+  constexpr int PW = fast_patch_words_sym(NS);
+  constexpr int N16 = PW * (int)sizeof(TS) / 16;
+  __shared__ uint4 As[N16];
+  __shared__ double rs[NS];
+  const int lane = threadIdx.x;
+  const int p = blockIdx.x;
+  const uint4* src = (const uint4*)(Pp + (long)p * PW);
+#pragma unroll
+  for (int j = lane; j < N16; j += 64) As[j] = src[j];
+  int f = -1;
+  if (lane < NS) {
+    const int c = lane % M2;
+    f = pf[(lane / M2) * np + p];
+    double r = 0.0;
+    if (f >= 0) {
+      r = b[(long)f * M2 + c];
+      if (yF) r -= yF[(long)(2 * f) * M2 + c] + yF[(long)(2 * f + 1) * M2 + c];
+    }
+    rs[lane] = r;
   }
-  const int i = threadIdx.x / PB, lp = threadIdx.x % PB, c = i % M2;
-  const int p = blockIdx.x * PB + lp;
-  const bool on = p < np;
-  const int f = on ? pf[(i / M2) * np + p] : -1;
-  double r = 0.0;
-  if (f >= 0) {
-    r = b[(long)f * M2 + c];
-    if (yF) r -= yF[(long)(2 * f) * M2 + c] + yF[(long)(2 * f + 1) * M2 + c];
-  }
-  rs[i * PB + lp] = r;
   __syncthreads();
-  if (!on) return;
-  const double* Pq = Pp + p;
-  const double* rq = rs + lp;
+  if (lane >= NS) return;
+  const TS* A = (const TS*)As;
+  const int i = lane;
+  const int rowi = i * NS - i * (i - 1) / 2 - i;  // e(i, j) = rowi + j for j >= i
   double d = 0.0;
 #pragma unroll
-  for (int t = 0; t < NS; ++t) {
-    const uint2 o = tab[t * NS + i];
-    d += Pq[o.x] * rq[o.y];
+  for (int j = 0; j < NS; ++j) {
+    const int colj = j * NS - j * (j - 1) / 2 - j;  // e(j, i) = colj + i for j < i
+    const int e = j < i ? colj + i : rowi + j;
+    d += (double)A[e] * rs[j];
   }
-  if (f >= 0) x[(long)f * M2 + c] += d;
+  if (sc) d *= (double)sc[p];
+  if (f >= 0) x[(long)f * M2 + i % M2] += d;
 }
 
 // Full row-major cell blocks -> packed SoA in groups of G (G = 2 for the
@@ -332,8 +331,8 @@ __global__ void k_pack_patches(int np, int gp0, int m2, const int* __restrict__ 
       Pp[((long)j * np + p) * NS + i] = (i < ns && j < ns) ? (TS)A[(long)j * ns + i] : (TS)0;
 }
 
-// Column-major per-patch inverses -> symmetric upper-triangle layout (the
-// mean of the two computed entries).
+// Column-major per-patch inverses -> upper triangles, patch p at
+// Pp[p * PW ...] (the mean of the two computed entries; zero padding).
 template <typename TS>
 __global__ void k_pack_patches_sym(int np, int gp0, int m2, const int* __restrict__ pf_ptr,
                                    const long* __restrict__ pinv_off, const double* __restrict__ pinv,
@@ -343,11 +342,29 @@ __global__ void k_pack_patches_sym(int np, int gp0, int m2, const int* __restric
   const int gp = gp0 + p;
   const int ns = (pf_ptr[gp + 1] - pf_ptr[gp]) * m2;
   const int NS = FAST_NF * m2;
+  const long PW = fast_patch_words_sym(NS);
   const double* A = pinv + pinv_off[gp];
+  TS* out = Pp + (long)p * PW;
   long e = 0;
   for (int a = 0; a < NS; ++a)
     for (int c = a; c < NS; ++c, ++e)
-      Pp[e * np + p] = (a < ns && c < ns) ? (TS)(0.5 * (A[(long)c * ns + a] + A[(long)a * ns + c])) : (TS)0;
+      out[e] = (a < ns && c < ns) ? (TS)(0.5 * (A[(long)c * ns + a] + A[(long)a * ns + c])) : (TS)0;
+  for (; e < PW; ++e) out[e] = (TS)0;
+}
+
+// FP64 upper triangles -> FP16, each divided by its largest magnitude
+// (kept in sc[p]).
+__global__ void k_patches_sym_f16(int np, int m2, const double* __restrict__ Pp, _Float16* __restrict__ P16,
+                                  float* __restrict__ sc) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  const long PW = fast_patch_words_sym(FAST_NF * m2);
+  const double* in = Pp + (long)p * PW;
+  double mx = 0.0;
+  for (long e = 0; e < PW; ++e) mx = fmax(mx, fabs(in[e]));
+  const double f = mx > 0.0 ? mx : 1.0;
+  sc[p] = (float)f;
+  for (long e = 0; e < PW; ++e) P16[(long)p * PW + e] = (_Float16)(in[e] / f);
 }
 
 inline int nblk(long n, int t = 256) { return (int)((n + t - 1) / t); }
@@ -380,19 +397,16 @@ void cell_apply_t(hipStream_t st, int m2, int nc, const TS* Sp, const int* cdof,
 template <typename TS>
 void patch_relax_t(hipStream_t st, int m2, int np, const int* pf, const TS* Pp, const double* b, const double* yF,
                    double* x, bool full, const float* sc) {
-  if constexpr (std::is_same<TS, double>::value) {
-    if (!full) {
-      switch (m2) {
-#define CASE(M)                                                                                            \
-  case M:                                                                                                  \
-    hipLaunchKernelGGL((k_patch_relax_sym<M>), dim3((np + SYM_PB - 1) / SYM_PB), dim3(FAST_NF * M * SYM_PB), 0, st, \
-                       np, pf, Pp, b, yF, x);                                                              \
+  if (!full) {
+    switch (m2) {
+#define CASE(M)                                                                                                \
+  case M:                                                                                                      \
+    hipLaunchKernelGGL((k_patch_relax_wave<M, TS>), dim3(np), dim3(64), 0, st, np, pf, Pp, b, yF, x, sc);      \
     break;
-        CASE(2) CASE(4) CASE(6) CASE(8) CASE(10)
+      CASE(2) CASE(4) CASE(6) CASE(8) CASE(10)
 #undef CASE
-      }
-      return;
     }
+    return;
   }
   switch (m2) {
 #define CASE(M)                                                                                            \
@@ -444,9 +458,12 @@ void launch_cells_f16(hipStream_t st, int nc, int m2, const double* Sp, const in
                        al);
 }
 
-void launch_patches_f16(hipStream_t st, int np, int m2, const double* Pp, _Float16* P16, float* sc) {
-  if (np > 0)
+void launch_patches_f16(hipStream_t st, int np, int m2, const double* Pp, _Float16* P16, float* sc, bool full) {
+  if (np <= 0) return;
+  if (full)
     hipLaunchKernelGGL(k_patches_f16, dim3(nblk(np)), dim3(256), 0, st, np, FAST_NF * m2, Pp, P16, sc);
+  else
+    hipLaunchKernelGGL(k_patches_sym_f16, dim3(nblk(np)), dim3(256), 0, st, np, m2, Pp, P16, sc);
 }
 
 void launch_regroup_cells_f32(hipStream_t st, int nc, int nK, const double* Sp, float* Sp32) {

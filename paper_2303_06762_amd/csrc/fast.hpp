@@ -22,12 +22,14 @@ inline long fast_cell_words(int nK, bool full = false) {
 }
 inline long fast_cell_words16(int nK) { return ((long)nK * (nK + 1) / 2 + 7) / 8 * 8; }
 
-// Patch-inverse storage: the upper triangle of each zero-padded FAST_NF*m2
-// square inverse (full = false: symmetric operators, FP64 only), else the
-// square.
+// Patch-inverse storage of the zero-padded NS = FAST_NF*m2 square inverses:
+// symmetric operators (full = false) the upper triangle, patch after patch,
+// NS(NS+1)/2 words rounded up to a multiple of 8 (16-byte aligned in every
+// precision); else the square.
+__host__ __device__ constexpr int fast_patch_words_sym(int ns) { return (ns * (ns + 1) / 2 + 7) / 8 * 8; }
 inline long fast_patch_words(int m2, bool full) {
   const long ns = (long)FAST_NF * m2;
-  return full ? ns * ns : ns * (ns + 1) / 2;
+  return full ? ns * ns : fast_patch_words_sym((int)ns);
 }
 
 // y_F[(2F+side)*m2 + c] = rows of S_K x_K for every cell K (m2 = 2 modes
@@ -41,8 +43,8 @@ void launch_cell_apply(hipStream_t st, int m2, int nc, const TS* Sp, const int* 
 void launch_facet_sum(hipStream_t st, int nint, int m2, const double* yF, const double* b, double alpha,
                       double* y);
 // x_s += A_ss^-1 (b - y)_s for the np patches of one colour (Pp in the
-// layout fast_patch_words(m2, full) describes; full = false only for TS =
-// double); yF null: y = 0
+// layout fast_patch_words(m2, full) describes; sc: per-patch scales of FP16
+// inverses, else null); yF null: y = 0
 template <typename TS>
 void launch_patch_relax(hipStream_t st, int m2, int np, const int* pf, const TS* Pp, const double* b,
                         const double* yF, double* x, bool full = true, const float* sc = nullptr);
@@ -56,9 +58,10 @@ void launch_pack_patches(hipStream_t st, int np, int gp0, int m2, const int* pf_
 // augmented-Lagrangian term eps^-1 |K|^-1 d d^T (d_i = cdiv[3K+i] on the
 // mode-0 normal unknowns) and without boundary rows and columns, divided by
 // its largest magnitude s; al[K] = (s, sqrt(eps^-1/|K|) d_0, .. d_1, .. d_2).
-// Full patch inverses: each divided by its largest magnitude (sc: np floats).
+// Patch inverses (full or upper-triangle layout, as Pp): each divided by its
+// largest magnitude (sc: np floats).
 void launch_cells_f16(hipStream_t st, int nc, int m2, const double* Sp, const int* cdof, const double* cdiv,
                       const double* area, double eps_inv, _Float16* Sp16, float4* al);
-void launch_patches_f16(hipStream_t st, int np, int m2, const double* Pp, _Float16* P16, float* sc);
+void launch_patches_f16(hipStream_t st, int np, int m2, const double* Pp, _Float16* P16, float* sc, bool full);
 
 }  // namespace hdgmg

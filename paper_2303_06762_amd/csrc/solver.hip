@@ -386,13 +386,8 @@ hdgmg_status upload_level(hdgmg_ctx* ctx, const Level& L, int m, DevLevel& D) {
     const double ws = vc_f32(ctx) ? 4.0 : 8.0;
     D.bytes_cell_vc = (double)L.nc * D.sp_words * ws + vec;
     D.bytes_sum = 3.0 * L.nint * m2 * 8.0;
-    // symmetric FP64 patch inverses are stored as upper triangles, addressed
-    // with 32-bit offsets (the FP32 copies of the mixed V-cycle stay square:
-    // their streaming relaxation is faster than the triangular one)
-    int np_max = 0;
-    for (int cc = 0; cc < L.ncol; ++cc) np_max = std::max(np_max, L.colour_ptr[cc + 1] - L.colour_ptr[cc]);
-    D.pfull = D.full || vc_f32(ctx) ||
-              (long)np_max * fast_patch_words(m2, false) >= (1L << 31);
+    // symmetric patch inverses are stored as upper triangles
+    D.pfull = D.full;
     const long pw = fast_patch_words(m2, D.pfull);
     for (int cc = 0; cc < L.ncol; ++cc) {
       int p0 = L.colour_ptr[cc], np = L.colour_ptr[cc + 1] - p0;
@@ -480,7 +475,7 @@ hdgmg_status make_f32(hdgmg_ctx* ctx, DevLevel& D, bool order_k = false) {
       TRY(dalloc(ctx, &D.Pp32[c], (size_t)n));
       launch_to_f32(ctx->st, n, D.Ppc[c], D.Pp32[c]);
     }
-    if (order_k && ctx->opts.vcycle_precision == 2 && fast_cell_packed(D.nK, D.full) && D.pfull) {
+    if (order_k && ctx->opts.vcycle_precision == 2 && fast_cell_packed(D.nK, D.full)) {
       D.f16 = true;
       TRY(dalloc(ctx, &D.Sp16, (size_t)D.nc * fast_cell_words16(D.nK)));
       TRY(dalloc(ctx, &D.al16, (size_t)D.nc));
@@ -491,7 +486,7 @@ hdgmg_status make_f32(hdgmg_ctx* ctx, DevLevel& D, bool order_k = false) {
         const int np = std::max(D.npc[c], 1);
         TRY(dalloc(ctx, &D.Pp16[c], (size_t)np * pw));
         TRY(dalloc(ctx, &D.psc16[c], (size_t)np));
-        launch_patches_f16(ctx->st, D.npc[c], 2 * D.m, D.Ppc[c], D.Pp16[c], D.psc16[c]);
+        launch_patches_f16(ctx->st, D.npc[c], 2 * D.m, D.Ppc[c], D.Pp16[c], D.psc16[c], D.pfull);
       }
       // the preconditioner's bytes: halves plus one scale per block
       const double vec = D.bytes_cell_vc - (double)D.nc * D.sp_words * 4.0;
@@ -549,7 +544,8 @@ void sweep(hdgmg_ctx* ctx, DevLevel& D, double* x, const double* b, bool forward
       const double* yF = skip ? nullptr : D.yF;
       t = kt_begin(ctx, level < 0 ? 0 : 2);
       if (D.f16)
-        launch_patch_relax<_Float16>(ctx->st, 2 * D.m, D.npc[c], D.pfc[c], D.Pp16[c], b, yF, x, true, D.psc16[c]);
+        launch_patch_relax<_Float16>(ctx->st, 2 * D.m, D.npc[c], D.pfc[c], D.Pp16[c], b, yF, x, D.pfull,
+                                     D.psc16[c]);
       else if (D.f32)
         launch_patch_relax<float>(ctx->st, 2 * D.m, D.npc[c], D.pfc[c], D.Pp32[c], b, yF, x, D.pfull);
       else
