@@ -193,31 +193,35 @@ __global__ void __launch_bounds__(256) k_patch_relax(int np, const int* __restri
 // the triangle: entry (i, j) at e(min(i, j), max(i, j)), e(a, b) = a NS -
 // a (a - 1) / 2 + b - a.  Every entry crosses HBM once.  sc: per-patch
 // scale of FP16 triangles, else null.
-template <int M2, typename TS>
+template <int M2, typename TS, bool HY>
 __global__ void __launch_bounds__(64) k_patch_relax_wave(int np, const int* __restrict__ pf, const TS* __restrict__ Pp,
                                                          const double* __restrict__ b, const double* __restrict__ yF,
                                                          double* __restrict__ x, const float* __restrict__ sc) {
   constexpr int NS = FAST_NF * M2;
   constexpr int PW = fast_patch_words_sym(NS);
   constexpr int N16 = PW * (int)sizeof(TS) / 16;
-  __shared__ uint4 As[N16];
+  constexpr int NL = (N16 + 63) / 64;
+  __shared__ uint4 As[NL * 64];
   __shared__ double rs[NS];
   const int lane = threadIdx.x;
   const int p = blockIdx.x;
+  const int f = lane < NS ? pf[(lane / M2) * np + p] : -1;
+  // every load of the triangle in flight before the first LDS store
   const uint4* src = (const uint4*)(Pp + (long)p * PW);
+  uint4 w[NL];
 #pragma unroll
-  for (int j = lane; j < N16; j += 64) As[j] = src[j];
-  int f = -1;
-  if (lane < NS) {
-    const int c = lane % M2;
-    f = pf[(lane / M2) * np + p];
-    double r = 0.0;
-    if (f >= 0) {
-      r = b[(long)f * M2 + c];
-      if (yF) r -= yF[(long)(2 * f) * M2 + c] + yF[(long)(2 * f + 1) * M2 + c];
-    }
-    rs[lane] = r;
+  for (int q = 0; q < NL; ++q) w[q] = src[min(lane + 64 * q, N16 - 1)];
+  // the residual's gathers without branches (row 0 stands in for padding)
+  const int fc = f >= 0 ? f : 0, c = lane % M2;
+  const double bv = b[(long)fc * M2 + c];
+  double y0 = 0.0, y1 = 0.0;
+  if constexpr (HY) {
+    y0 = yF[(long)(2 * fc) * M2 + c];
+    y1 = yF[(long)(2 * fc + 1) * M2 + c];
   }
+#pragma unroll
+  for (int q = 0; q < NL; ++q) As[lane + 64 * q] = w[q];  // slots past N16 are never read
+  if (lane < NS) rs[lane] = f >= 0 ? bv - (y0 + y1) : 0.0;
   __syncthreads();
   if (lane >= NS) return;
   const TS* A = (const TS*)As;
@@ -401,7 +405,10 @@ void patch_relax_t(hipStream_t st, int m2, int np, const int* pf, const TS* Pp, 
     switch (m2) {
 #define CASE(M)                                                                                                \
   case M:                                                                                                      \
-    hipLaunchKernelGGL((k_patch_relax_wave<M, TS>), dim3(np), dim3(64), 0, st, np, pf, Pp, b, yF, x, sc);      \
+    if (yF)                                                                                                    \
+      hipLaunchKernelGGL((k_patch_relax_wave<M, TS, true>), dim3(np), dim3(64), 0, st, np, pf, Pp, b, yF, x, sc); \
+    else                                                                                                       \
+      hipLaunchKernelGGL((k_patch_relax_wave<M, TS, false>), dim3(np), dim3(64), 0, st, np, pf, Pp, b, yF, x, sc); \
     break;
       CASE(2) CASE(4) CASE(6) CASE(8) CASE(10)
 #undef CASE
