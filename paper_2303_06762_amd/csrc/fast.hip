@@ -187,32 +187,44 @@ __global__ void __launch_bounds__(256) k_patch_relax(int np, const int* __restri
 }
 
 // The same relaxation from the upper triangles of symmetric inverses, a
-// wavefront per patch: the patch's triangle (contiguous, PW words) is read
-// once with 16-byte loads by all 64 lanes into LDS, the patch residual goes
-// to LDS, and lane i < NS forms row i of the inverse times the residual from
-// the triangle: entry (i, j) at e(min(i, j), max(i, j)), e(a, b) = a NS -
-// a (a - 1) / 2 + b - a.  Every entry crosses HBM once.  sc: per-patch
-// scale of FP16 triangles, else null.
+// wavefront per patch (per 64 / NS consecutive patches when NS <= 32): the
+// triangles (contiguous, PW words each) are read once with 16-byte loads by
+// all 64 lanes into LDS, the patch residuals go to LDS, and lane (patch,
+// row i) forms row i of the inverse times the residual from the triangle:
+// entry (i, j) at e(min(i, j), max(i, j)), e(a, b) = a NS - a (a - 1) / 2 +
+// b - a.  Every entry crosses HBM once.  sc: per-patch scale of FP16
+// triangles, else null.
+template <int M2>
+struct WaveShape {
+  static constexpr int NS = FAST_NF * M2;
+  static constexpr int PPW = NS <= 32 ? 64 / NS : 1;  // patches per wavefront
+};
 template <int M2, typename TS, bool HY>
 __global__ void __launch_bounds__(64) k_patch_relax_wave(int np, const int* __restrict__ pf, const TS* __restrict__ Pp,
                                                          const double* __restrict__ b, const double* __restrict__ yF,
                                                          double* __restrict__ x, const float* __restrict__ sc) {
-  constexpr int NS = FAST_NF * M2;
+  constexpr int NS = FAST_NF * M2, PPW = WaveShape<M2>::PPW;
   constexpr int PW = fast_patch_words_sym(NS);
-  constexpr int N16 = PW * (int)sizeof(TS) / 16;
+  constexpr int N16 = PPW * PW * (int)sizeof(TS) / 16;  // the wavefront's triangles
   constexpr int NL = (N16 + 63) / 64;
   __shared__ uint4 As[NL * 64];
-  __shared__ double rs[NS];
+  __shared__ double rs[PPW * NS];
   const int lane = threadIdx.x;
-  const int p = blockIdx.x;
-  const int f = lane < NS ? pf[(lane / M2) * np + p] : -1;
-  // every load of the triangle in flight before the first LDS store
-  const uint4* src = (const uint4*)(Pp + (long)p * PW);
+  const int lp = lane / NS, i = lane % NS;  // patch of the wavefront, row
+  const int p0 = blockIdx.x * PPW;
+  const int p = p0 + lp;
+  const bool on = lp < PPW && p < np;
+  const int f = on ? pf[(i / M2) * np + p] : -1;
+  // every load of the triangles in flight before the first LDS store (the
+  // last patches of the colour re-read the final triangle)
+  const long last16 = (long)np * PW * (long)sizeof(TS) / 16 - 1;
+  const uint4* src = (const uint4*)(Pp + (long)p0 * PW);
+  const long rem = last16 - (long)p0 * PW * (long)sizeof(TS) / 16;
   uint4 w[NL];
 #pragma unroll
-  for (int q = 0; q < NL; ++q) w[q] = src[min(lane + 64 * q, N16 - 1)];
+  for (int q = 0; q < NL; ++q) w[q] = src[min((long)min(lane + 64 * q, N16 - 1), rem)];
   // the residual's gathers without branches (row 0 stands in for padding)
-  const int fc = f >= 0 ? f : 0, c = lane % M2;
+  const int fc = f >= 0 ? f : 0, c = i % M2;
   const double bv = b[(long)fc * M2 + c];
   double y0 = 0.0, y1 = 0.0;
   if constexpr (HY) {
@@ -221,21 +233,21 @@ __global__ void __launch_bounds__(64) k_patch_relax_wave(int np, const int* __re
   }
 #pragma unroll
   for (int q = 0; q < NL; ++q) As[lane + 64 * q] = w[q];  // slots past N16 are never read
-  if (lane < NS) rs[lane] = f >= 0 ? bv - (y0 + y1) : 0.0;
+  if (lp < PPW) rs[lane] = f >= 0 ? bv - (y0 + y1) : 0.0;
   __syncthreads();
-  if (lane >= NS) return;
-  const TS* A = (const TS*)As;
-  const int i = lane;
+  if (!on) return;
+  const TS* A = (const TS*)As + lp * PW;
+  const double* r = rs + lp * NS;
   const int rowi = i * NS - i * (i - 1) / 2 - i;  // e(i, j) = rowi + j for j >= i
   double d = 0.0;
 #pragma unroll
   for (int j = 0; j < NS; ++j) {
     const int colj = j * NS - j * (j - 1) / 2 - j;  // e(j, i) = colj + i for j < i
     const int e = j < i ? colj + i : rowi + j;
-    d += (double)A[e] * rs[j];
+    d += (double)A[e] * r[j];
   }
   if (sc) d *= (double)sc[p];
-  if (f >= 0) x[(long)f * M2 + i % M2] += d;
+  if (f >= 0) x[(long)f * M2 + c] += d;
 }
 
 // Full row-major cell blocks -> packed SoA in groups of G (G = 2 for the
@@ -406,9 +418,11 @@ void patch_relax_t(hipStream_t st, int m2, int np, const int* pf, const TS* Pp, 
 #define CASE(M)                                                                                                \
   case M:                                                                                                      \
     if (yF)                                                                                                    \
-      hipLaunchKernelGGL((k_patch_relax_wave<M, TS, true>), dim3(np), dim3(64), 0, st, np, pf, Pp, b, yF, x, sc); \
+      hipLaunchKernelGGL((k_patch_relax_wave<M, TS, true>), dim3((np + WaveShape<M>::PPW - 1) / WaveShape<M>::PPW), \
+                         dim3(64), 0, st, np, pf, Pp, b, yF, x, sc);                                          \
     else                                                                                                       \
-      hipLaunchKernelGGL((k_patch_relax_wave<M, TS, false>), dim3(np), dim3(64), 0, st, np, pf, Pp, b, yF, x, sc); \
+      hipLaunchKernelGGL((k_patch_relax_wave<M, TS, false>), dim3((np + WaveShape<M>::PPW - 1) / WaveShape<M>::PPW), \
+                         dim3(64), 0, st, np, pf, Pp, b, yF, x, sc);                                          \
     break;
       CASE(2) CASE(4) CASE(6) CASE(8) CASE(10)
 #undef CASE
