@@ -525,10 +525,12 @@ __global__ void __launch_bounds__(64) k_gs(LevelViewT<TS> L, int p0, double* x, 
   }
 }
 
-__global__ void k_mode0_extract(int nint, int m, const double* __restrict__ r, double* __restrict__ g0) {
+__global__ void k_mode0_extract(int nint, int m, const double* __restrict__ r, double* __restrict__ g0,
+                                double* __restrict__ zero_out) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= 2 * nint) return;
   g0[t] = r[(long)t * m];
+  if (zero_out) zero_out[t] = 0.0;
 }
 
 __global__ void k_mode0_add(int nint, int m, const double* __restrict__ u0, double* __restrict__ x) {
@@ -554,9 +556,11 @@ __global__ void k_spmv(int nrows, const int* __restrict__ rp, const int* __restr
 // and count zero.
 template <typename TS>
 __global__ void k_ell_spmv(int n, int w, const int* __restrict__ ci, const TS* __restrict__ v,
-                           const double* __restrict__ x, double* y, double beta_y) {
+                           const double* __restrict__ x, double* y, double beta_y, double* zero_out) {
   int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n || w <= 0) return;
+  if (r >= n) return;
+  if (zero_out) zero_out[r] = 0.0;
+  if (w <= 0) return;
   double s = 0.0;
   for (int k0 = 0; k0 < w; k0 += 8) {
     TS vv[8];
@@ -828,9 +832,9 @@ void launch_gs(hipStream_t st, LevelViewT<TS> L, int p0, int p1, double* x, cons
 }
 template void launch_gs<double>(hipStream_t, LevelViewT<double>, int, int, double*, const double*);
 template void launch_gs<float>(hipStream_t, LevelViewT<float>, int, int, double*, const double*);
-void launch_mode0_extract(hipStream_t st, int nint, int m, const double* r, double* g0) {
+void launch_mode0_extract(hipStream_t st, int nint, int m, const double* r, double* g0, double* zero_out) {
   if (nint <= 0) return;
-  hipLaunchKernelGGL(k_mode0_extract, dim3(nblk(2L * nint)), dim3(TPB), 0, st, nint, m, r, g0);
+  hipLaunchKernelGGL(k_mode0_extract, dim3(nblk(2L * nint)), dim3(TPB), 0, st, nint, m, r, g0, zero_out);
 }
 void launch_mode0_add(hipStream_t st, int nint, int m, const double* u0, double* x) {
   if (nint <= 0) return;
@@ -843,14 +847,14 @@ void launch_spmv(hipStream_t st, int nrows, const int* rp, const int* ci, const 
 }
 template <typename TS>
 void launch_ell_spmv(hipStream_t st, int n, int w, const int* ci, const TS* v, const double* x, double* y,
-                     double beta_y) {
+                     double beta_y, double* zero_out) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_ell_spmv<TS>, dim3(nblk(n)), dim3(TPB), 0, st, n, w, ci, v, x, y, beta_y);
+  hipLaunchKernelGGL(k_ell_spmv<TS>, dim3(nblk(n)), dim3(TPB), 0, st, n, w, ci, v, x, y, beta_y, zero_out);
 }
 template void launch_ell_spmv<double>(hipStream_t, int, int, const int*, const double*, const double*, double*,
-                                      double);
+                                      double, double*);
 template void launch_ell_spmv<float>(hipStream_t, int, int, const int*, const float*, const double*, double*,
-                                     double);
+                                     double, double*);
 template <typename TS>
 void launch_gemv_dense(hipStream_t st, int n, const TS* A, const double* x, double* y) {
   if (n <= 0) return;

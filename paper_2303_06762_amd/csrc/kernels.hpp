@@ -99,13 +99,17 @@ template <typename TS>
 void launch_gs(hipStream_t st, LevelViewT<TS> L, int p0, int p1, double* x, const double* b);
 // out[i] = (float) in[i]
 void launch_to_f32(hipStream_t st, long n, const double* in, float* out);
-void launch_mode0_extract(hipStream_t st, int nint, int m, const double* r, double* g0);
+// g0 = mode 0 of r (restriction to the lowest-order space); zero_out (if not
+// null) is set to zero over the same 2 nint entries.
+void launch_mode0_extract(hipStream_t st, int nint, int m, const double* r, double* g0, double* zero_out = nullptr);
 void launch_mode0_add(hipStream_t st, int nint, int m, const double* u0, double* x);
 void launch_spmv(hipStream_t st, int nrows, const int* rp, const int* ci, const double* v,
                  const double* x, double* y, double beta_y);
+// y = A x + beta_y y for an ELL matrix (n rows, width w); zero_out (if not
+// null) is set to zero over the same n rows.
 template <typename TS>
 void launch_ell_spmv(hipStream_t st, int n, int w, const int* ci, const TS* v, const double* x, double* y,
-                     double beta_y);
+                     double beta_y, double* zero_out = nullptr);
 template <typename TS>
 void launch_gemv_dense(hipStream_t st, int n, const TS* A, const double* x, double* y);
 void launch_fill(hipStream_t st, long n, double v, double* x);

@@ -622,10 +622,9 @@ void mg_h(hdgmg_ctx* ctx, int l, int m_l, bool u_zero) {
   DevTransfer& T = ctx->tr[l];
   DevLevel& C = ctx->cr[l - 1];
   if (vc_f32(ctx))
-    launch_ell_spmv<float>(ctx->st, T.ncoarse, T.Rw, T.Re_ci, T.Re_v32, D.r, C.g, 0.0);
+    launch_ell_spmv<float>(ctx->st, T.ncoarse, T.Rw, T.Re_ci, T.Re_v32, D.r, C.g, 0.0, C.u);
   else
-    launch_ell_spmv<double>(ctx->st, T.ncoarse, T.Rw, T.Re_ci, T.Re_v, D.r, C.g, 0.0);
-  launch_fill(ctx->st, C.ndof, 0.0, C.u);
+    launch_ell_spmv<double>(ctx->st, T.ncoarse, T.Rw, T.Re_ci, T.Re_v, D.r, C.g, 0.0, C.u);  // and C.u = 0
   for (int n = 0; n < ctx->opts.cycle; ++n) mg_h(ctx, l - 1, ctx->opts.vcycle_growth * m_l, n == 0);
   if (vc_f32(ctx))
     launch_ell_spmv<float>(ctx->st, T.nfine, T.Pw, T.Pe_ci, T.Pe_v32, C.u, D.u, 1.0);
@@ -696,8 +695,7 @@ void mg_hp_body(hdgmg_ctx* ctx, const double* r, double* z) {
   launch_fill(ctx->st, KL.ndof, 0.0, z);
   for (int s = 0; s < ctx->opts.m_relax; ++s) sweep(ctx, KL, z, r, true, -1, s == 0);
   apply_k(ctx, z, KL.r, -1.0, r, true);
-  launch_mode0_extract(ctx->st, KL.nint, KL.m, KL.r, DJ.g);
-  launch_fill(ctx->st, DJ.ndof, 0.0, DJ.u);
+  launch_mode0_extract(ctx->st, KL.nint, KL.m, KL.r, DJ.g, DJ.u);  // and DJ.u = 0
   mg_h(ctx, ctx->J - 1, ctx->opts.m_smooth, true);
   launch_mode0_add(ctx->st, KL.nint, KL.m, DJ.u, z);
   for (int s = 0; s < ctx->opts.m_relax; ++s) sweep(ctx, KL, z, r, false, -1);
