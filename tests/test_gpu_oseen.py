@@ -137,13 +137,15 @@ def test_oseen_full_solve(name):
     s.close()
 
 
-def test_oseen_mixed_precision():
+@pytest.mark.parametrize("prec", [1, 2])
+def test_oseen_mixed_precision(prec):
+    # precision 2 keeps FP32 for the nonsymmetric (full) order-k blocks
     import paper_2303_06762_amd as hd
     name = "k2_stream"
     c, t, levels, S, wq, f, dirichlet = oracle_case(name)
     n, nr, k, nu, beta, scale, lid, kw = CASES[name]
-    _note("oseen mixed precision")
-    s = hd.Solver(c, t, nr, k, beta, nu, 1e2, oseen=1, vcycle_precision=1, stream_dofs=0)
+    _note(f"oseen mixed precision {prec}")
+    s = hd.Solver(c, t, nr, k, beta, nu, 1e2, oseen=1, vcycle_precision=prec, stream_dofs=0)
     s.set_wind(dev(wq))
     s.assemble()
     b = synth.uniform_pm1(12, 0, s.n_skel)

@@ -89,6 +89,10 @@ CASES = {
     "k2_stream": (lambda: synth.kuhn_square(4), 2, 2, 1.0, 1.0, 1e2, dict(stream_dofs=0, coarse_dofs=400)),
     "k3_stream": (lambda: synth.kuhn_square(4), 1, 3, 1.0, 0.0, 1e4, dict(stream_dofs=0)),
     "k4_stream": (lambda: jittered_square(4, 5), 1, 4, 0.7, 2.0, 1e2, dict(stream_dofs=0)),
+    # streaming layout on every level, but the lowest-order levels outside the
+    # coarse kernel smooth with the record kernel (residuals stay streamed)
+    "k1_stream_rec": (lambda: synth.kuhn_square(4), 2, 1, 1.0, 1.0, 1e2, dict(stream_dofs=1, coarse_dofs=200)),
+    "k2_stream_rec": (lambda: synth.kuhn_square(4), 2, 2, 0.8, 0.5, 1e2, dict(stream_dofs=1, coarse_dofs=0)),
 }
 
 
@@ -128,7 +132,9 @@ def test_rhs_and_preconditioner(name):
     assert rel(g, O.prob.rhs(f)) < 1e-10
     r = synth.uniform_pm1(22, 0, (G.n_skel,))
     z = host(G.precondition(dev(r)))
-    assert rel(z, O.prec(r)) < 1e-10
+    err = rel(z, O.prec(r))
+    _note(f"  preconditioner rel. difference {err:.2e}")
+    assert err < 1e-10
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -142,10 +148,18 @@ def test_inner_solve(name):
     x_o, its_o, hist = O.inner(g)
     x, its, relres, st = G.inner_solve(dev(g))
     x = host(x)
+    diff = np.linalg.norm(x - x_o) / np.linalg.norm(x_o)
+    _note(f"  its {its} (oracle {its_o}), solution rel. difference {diff:.2e}")
     assert st == 0
     assert abs(its - its_o) <= 1, (its, its_o)
     assert relres <= 1e-8 or relres * np.linalg.norm(g) <= 1e-10
-    assert np.linalg.norm(x - x_o) <= 1e-9 * np.linalg.norm(x_o)
+    if its == its_o:
+        # the same iterations: the two differ by rounding only
+        assert diff <= 1e-9, (its, diff)
+    else:
+        # one iteration apart, both at the stopping tolerance: the GPU
+        # iterate meets it on the oracle's FP64 operator
+        assert np.linalg.norm(g - O.Aeps @ x) <= 1.5e-8 * np.linalg.norm(g), (its, its_o, diff)
 
 
 @pytest.mark.parametrize("name", ["k0", "k2", "beta0_gamma1e4", "jittered_k2", "one_level_k2",
