@@ -539,16 +539,6 @@ __global__ void k_mode0_add(int nint, int m, const double* __restrict__ u0, doub
   x[(long)t * m] += u0[t];
 }
 
-__global__ void k_spmv(int nrows, const int* __restrict__ rp, const int* __restrict__ ci,
-                       const double* __restrict__ v, const double* __restrict__ x, double* y,
-                       double beta_y) {
-  int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nrows) return;
-  double s = 0.0;
-  for (int q = rp[r]; q < rp[r + 1]; ++q) s += v[q] * x[ci[q]];
-  y[r] = beta_y == 0.0 ? s : beta_y * y[r] + s;
-}
-
 // ELL (padded, column-major) sparse matrix-vector product: entry k of row r
 // at [k * n + r], padding has value 0 and column 0.  Slots go in chunks of
 // eight, so that a thread has eight value and column loads, then eight
@@ -839,11 +829,6 @@ void launch_mode0_extract(hipStream_t st, int nint, int m, const double* r, doub
 void launch_mode0_add(hipStream_t st, int nint, int m, const double* u0, double* x) {
   if (nint <= 0) return;
   hipLaunchKernelGGL(k_mode0_add, dim3(nblk(2L * nint)), dim3(TPB), 0, st, nint, m, u0, x);
-}
-void launch_spmv(hipStream_t st, int nrows, const int* rp, const int* ci, const double* v, const double* x,
-                 double* y, double beta_y) {
-  if (nrows <= 0) return;
-  hipLaunchKernelGGL(k_spmv, dim3(nblk(nrows)), dim3(TPB), 0, st, nrows, rp, ci, v, x, y, beta_y);
 }
 template <typename TS>
 void launch_ell_spmv(hipStream_t st, int n, int w, const int* ci, const TS* v, const double* x, double* y,

@@ -103,8 +103,6 @@ void launch_to_f32(hipStream_t st, long n, const double* in, float* out);
 // null) is set to zero over the same 2 nint entries.
 void launch_mode0_extract(hipStream_t st, int nint, int m, const double* r, double* g0, double* zero_out = nullptr);
 void launch_mode0_add(hipStream_t st, int nint, int m, const double* u0, double* x);
-void launch_spmv(hipStream_t st, int nrows, const int* rp, const int* ci, const double* v,
-                 const double* x, double* y, double beta_y);
 // y = A x + beta_y y for an ELL matrix (n rows, width w); zero_out (if not
 // null) is set to zero over the same n rows.
 template <typename TS>
