@@ -16,6 +16,7 @@
 #include <cstring>
 #include <map>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/hdgmg.h"
@@ -878,18 +879,31 @@ hdgmg_status fgmres(hdgmg_ctx* ctx, const double* b, double* x, int* its_out, do
 hdgmg_status build_transfers(hdgmg_ctx* ctx) {
   ctx->tr.assign(ctx->J, DevTransfer());
   const bool general = ctx->opts.oseen != 0;
-  for (int l = 1; l < ctx->J; ++l) {
-    CSR P, R;
-    // prolongation harmonic for A; restriction the transpose of the same
-    // construction for A^T (the transpose of P when A is symmetric)
-    bool ok = stabilised_transfer(ctx->lv[l - 1], ctx->lv[l], ctx->avg[l], ctx->hostB[l], false, general, P);
-    if (ok && ctx->has_wind) {
-      CSR Pt;
-      ok = stabilised_transfer(ctx->lv[l - 1], ctx->lv[l], ctx->avg[l], ctx->hostB[l], true, general, Pt);
-      csr_transpose(Pt, 2 * ctx->lv[l - 1].nint, R);
-    } else {
-      csr_transpose(P, 2 * ctx->lv[l - 1].nint, R);
+  // host construction of every level's transfers at once (a thread per level
+  // and operator; the large levels split their coarse cells further)
+  const int J = ctx->J;
+  std::vector<CSR> Ps(J), Pts(J);
+  std::vector<char> okP(J, 1), okT(J, 1);
+  {
+    std::vector<std::thread> th;
+    for (int l = 1; l < J; ++l) {
+      // prolongation harmonic for A; restriction the transpose of the same
+      // construction for A^T (the transpose of P when A is symmetric)
+      th.emplace_back([&, l] {
+        okP[l] = stabilised_transfer(ctx->lv[l - 1], ctx->lv[l], ctx->avg[l], ctx->hostB[l], false, general, Ps[l]);
+      });
+      if (ctx->has_wind)
+        th.emplace_back([&, l] {
+          okT[l] = stabilised_transfer(ctx->lv[l - 1], ctx->lv[l], ctx->avg[l], ctx->hostB[l], true, general, Pts[l]);
+        });
     }
+    for (auto& t : th) t.join();
+  }
+  for (int l = 1; l < ctx->J; ++l) {
+    CSR& P = Ps[l];
+    CSR R;
+    bool ok = okP[l] && okT[l];
+    if (ok) csr_transpose(ctx->has_wind ? Pts[l] : P, 2 * ctx->lv[l - 1].nint, R);
     if (!ok) {
       ctx->err = "singular interior block in harmonic extension";
       return HDGMG_ENONFINITE;
@@ -956,23 +970,55 @@ hdgmg_status level_records(hdgmg_ctx* ctx, int l, int max_items, LevelRecords& R
   assemble_csr(L, ctx->hostB[l], A);
   R.rw_col.assign((size_t)COARSE_NNZ * n, 0);
   R.rw_val.assign((size_t)COARSE_NNZ * n, 0.0);
-  for (int i = 0; i < n; ++i) {
-    int nz = A.rp[i + 1] - A.rp[i];
-    if (nz > COARSE_NNZ) {
+  for (int i = 0; i < n; ++i)
+    if (A.rp[i + 1] - A.rp[i] > COARSE_NNZ) {
       ctx->err = "lowest-order row with more than 10 entries";
       return HDGMG_EMESH;
     }
-    for (int k = 0; k < nz; ++k) {
-      R.rw_col[(size_t)k * n + i] = A.ci[A.rp[i] + k];
-      R.rw_val[(size_t)k * n + i] = A.v[A.rp[i] + k];
-    }
-  }
+  for (int k = 0; k < COARSE_NNZ; ++k)  // entry-major: contiguous writes
+    for (int i = 0; i < n; ++i)
+      if (k < A.rp[i + 1] - A.rp[i]) {
+        R.rw_col[(size_t)k * n + i] = A.ci[A.rp[i] + k];
+        R.rw_val[(size_t)k * n + i] = A.v[A.rp[i] + k];
+      }
   const int nsm = 2 * L.max_patch_facets;
   R.nsm = nsm;
   R.cb.assign(1, 0);
   R.bitem.assign(1, 0);
+  // patch inverses (host FP64), patches split over threads; the unknown ->
+  // patch-row map of a thread marks the current patch's unknowns
+  const int npatch = L.colour_ptr[L.ncol];
+  std::vector<std::vector<double>> invs(npatch);
+  std::vector<char> pok(npatch, 1);
+  {
+    const int nth = npatch >= 1024 ? (int)std::min(16u, std::max(1u, std::thread::hardware_concurrency())) : 1;
+    std::vector<std::thread> th;
+    for (int w = 0; w < nth; ++w)
+      th.emplace_back([&, w] {
+        std::vector<int> slot(n, -1);
+        for (int p = w; p < npatch; p += nth) {
+          const int f0 = L.patch_facet_ptr[p], nfp = L.patch_facet_ptr[p + 1] - f0, ns = 2 * nfp;
+          for (int a = 0; a < ns; ++a) slot[2 * L.patch_facets[f0 + a / 2] + a % 2] = a;
+          std::vector<double> Ass((size_t)ns * ns, 0.0);
+          for (int i = 0; i < ns; ++i) {
+            const int di = 2 * L.patch_facets[f0 + i / 2] + i % 2;
+            for (int q = A.rp[di]; q < A.rp[di + 1]; ++q)
+              if (slot[A.ci[q]] >= 0) Ass[(size_t)i * ns + slot[A.ci[q]]] = A.v[q];
+          }
+          for (int a = 0; a < ns; ++a) slot[2 * L.patch_facets[f0 + a / 2] + a % 2] = -1;
+          pok[p] = ctx->opts.oseen ? invert_general(Ass, ns, invs[p]) : invert_spd(Ass, ns, invs[p]);
+        }
+      });
+    for (auto& t : th) t.join();
+  }
   std::vector<int> idof, iloc;
   std::vector<double> irow;  // [item][nsm]
+  {
+    const size_t items = (size_t)2 * L.patch_facet_ptr[npatch] * (pad ? 5 : 4) / 4;  // padding: about a quarter more
+    idof.reserve(items);
+    iloc.reserve(items);
+    irow.reserve(items * nsm);
+  }
   for (int c = 0; c < L.ncol; ++c) {
     for (int p = L.colour_ptr[c]; p < L.colour_ptr[c + 1]; ++p) {
       int f0 = L.patch_facet_ptr[p], nfp = L.patch_facet_ptr[p + 1] - f0;
@@ -980,15 +1026,11 @@ hdgmg_status level_records(hdgmg_ctx* ctx, int l, int max_items, LevelRecords& R
       std::vector<int> dofs(ns);
       for (int a = 0; a < nfp; ++a)
         for (int comp = 0; comp < 2; ++comp) dofs[2 * a + comp] = 2 * L.patch_facets[f0 + a] + comp;
-      std::vector<double> Ass((size_t)ns * ns, 0.0), inv;
-      for (int i = 0; i < ns; ++i)
-        for (int q = A.rp[dofs[i]]; q < A.rp[dofs[i] + 1]; ++q)
-          for (int j = 0; j < ns; ++j)
-            if (A.ci[q] == dofs[j]) Ass[(size_t)i * ns + j] = A.v[q];
-      if (!(ctx->opts.oseen ? invert_general(Ass, ns, inv) : invert_spd(Ass, ns, inv))) {
+      if (!pok[p]) {
         ctx->err = "singular patch block on a lowest-order level";
         return HDGMG_ENONFINITE;
       }
+      const std::vector<double>& inv = invs[p];
       if ((int)idof.size() - R.bitem.back() + ns > max_items) {
         while (pad && (int)idof.size() - R.bitem.back() < max_items) {
           idof.push_back(-1);
@@ -1030,11 +1072,14 @@ hdgmg_status level_records(hdgmg_ctx* ctx, int l, int max_items, LevelRecords& R
     // facet pairs (2F, 2F + 1), sorted, padded with zero entries
     R.meta[(size_t)t * 4] = (unsigned)idof[t] | ((unsigned)iloc[t] << REC_LOC_SHIFT);
     // values in groups of G: entry e of item t at [((e / G) * nit + t) * G + e % G]
-    for (int k = 0; k < COARSE_NNZ; ++k)
-      R.val[((size_t)(k / G) * nit + t) * G + k % G] = R.rw_val[(size_t)k * n + idof[t]];
+    // the row's entries straight from the CSR (contiguous), zero beyond its length
+    const int r0 = A.rp[idof[t]], nz = A.rp[idof[t] + 1] - r0;
+    auto col = [&](int k) { return k < nz ? A.ci[r0 + k] : 0; };
+    auto val = [&](int k) { return k < nz ? A.v[r0 + k] : 0.0; };
+    for (int k = 0; k < COARSE_NNZ; ++k) R.val[((size_t)(k / G) * nit + t) * G + k % G] = val(k);
     for (int q = 0; q < COARSE_NNZ / 2; ++q) {
-      const int c0 = R.rw_col[(size_t)(2 * q) * n + idof[t]], c1 = R.rw_col[(size_t)(2 * q + 1) * n + idof[t]];
-      const double v0 = R.rw_val[(size_t)(2 * q) * n + idof[t]], v1 = R.rw_val[(size_t)(2 * q + 1) * n + idof[t]];
+      const int c0 = col(2 * q), c1 = col(2 * q + 1);
+      const double v0 = val(2 * q), v1 = val(2 * q + 1);
       const bool padded = c0 == 0 && c1 == 0 && v0 == 0.0 && v1 == 0.0;
       if (!padded && (c0 % 2 != 0 || c1 != c0 + 1)) {
         ctx->err = "lowest-order row whose columns are not facet pairs";
