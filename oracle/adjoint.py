@@ -20,6 +20,14 @@ values gu / (w_q |K|).  Then
 (the only nu-dependent term of the system is the nu-weighted lifting
 energy; the augmented-Lagrangian weight is a fixed number and multiplies
 div u_h, which vanishes at the discrete solution).
+
+Oseen (Picard-linearised) systems at a fixed wind: the convection form makes
+the saddle point nonsymmetric, so the adjoint state solves the transposed
+system (convection transposed per cell, Stokes part and constraint
+unchanged) with the same load functional.  The two formulas above keep
+their form, with the adjoint's local fields recovered by the transposed
+local solve: dJ/dnu_K = -(Lift(z), Lift(z_adj))_K still holds because the
+convection form does not depend on nu.
 """
 import numpy as np
 
@@ -47,11 +55,12 @@ def lift_coefficients(e, z):
     return np.array([[Minv @ (e.R[i, j] @ z) for j in range(2)] for i in range(2)])
 
 
-def grad_nu_cell(e, lam_u, f_u, lam_a, f_a):
+def grad_nu_cell(e, lam_u, f_u, lam_a, f_a, e_adj=None):
     """-(Lift(z_u), Lift(z_a))_K for the local states recovered from the
-    skeleton values and sources of the forward and adjoint solves."""
+    skeleton values and sources of the forward and adjoint solves (e_adj:
+    the cell of the transposed system when it differs from e)."""
     z_u, _ = e.recover_z(lam_u, f_u)
-    z_a, _ = e.recover_z(lam_a, f_a)
+    z_a, _ = (e_adj or e).recover_z(lam_a, f_a)
     Lu = lift_coefficients(e, z_u)
     La = lift_coefficients(e, z_a)
     s = 0.0
@@ -66,22 +75,27 @@ def velocity(prob, lam, p0, f_qp):
     return u
 
 
-def gradients(prob, f_qp, ut_qp, solve=None):
+def gradients(prob, f_qp, ut_qp, solve=None, prob_adj=None, solve_adj=None):
     """(J, dJ/df [n_cells, n_q, 2], dJ/dnu [n_cells], adjoint (lam, p0)).
 
     solve(f_qp) -> (lam, p0) defaults to the direct solve of the condensed
-    saddle point (the dense adjoint); the method's solve can be passed in."""
+    saddle point (the dense adjoint); the method's solve can be passed in.
+    prob_adj / solve_adj: the transposed system and its solve, for
+    nonsymmetric (Oseen) problems; by default the forward ones."""
     solve = solve or prob.solve_direct
+    pa = prob_adj or prob
+    solve_adj = solve_adj or (pa.solve_direct if prob_adj is not None else solve)
     lam, p0 = solve(f_qp)
     u = velocity(prob, lam, p0, f_qp)
     J = misfit(prob, u, ut_qp)
     W = weights(prob)
     gu = misfit_grad(prob, u, ut_qp)
     f_adj = gu / W[:, :, None]
-    lam_a, p0_a = solve(f_adj)
-    u_a = velocity(prob, lam_a, p0_a, f_adj)
+    lam_a, p0_a = solve_adj(f_adj)
+    u_a = velocity(pa, lam_a, p0_a, f_adj)
     gf = W[:, :, None] * u_a
-    gnu = np.array([grad_nu_cell(e, prob.local(lam, K), f_qp[K], prob.local(lam_a, K), f_adj[K])
+    gnu = np.array([grad_nu_cell(e, prob.local(lam, K), f_qp[K], pa.local(lam_a, K), f_adj[K],
+                                 pa.elems[K] if prob_adj is not None else None)
                     for K, e in enumerate(prob.elems)])
     return J, gf, gnu, (lam_a, p0_a)
 

@@ -27,6 +27,12 @@ imports it).
   residual; x_0 = the latest skeleton iterate.
 * Tangential Dirichlet data on boundary facets (the lid of the cavity):
   uhat . t_F prescribed per boundary facet and mode; moved to the load.
+* Transposed (adjoint) systems, transpose=True: every cell's convection
+  matrix enters transposed (the Stokes part is symmetric), on the order-k
+  level and on every lowest-order level.  Static condensation commutes with
+  transposition, so the condensed operator, the patch blocks and the
+  harmonic transfers built from it are those of A^T; the AL weight and the
+  divergence constraint are symmetric and unchanged.
 """
 import math
 
@@ -149,13 +155,16 @@ def zero_wind(X):
 class OseenProblem(hdg.Problem):
     """Condensed Picard-linearised system on one level.  winds: one callable
     per cell (None: no convection).  dirichlet: [n_facets, k+1] tangential
-    coefficients on boundary facets (None: homogeneous)."""
+    coefficients on boundary facets (None: homogeneous).  transpose: the
+    transposed system (convection matrices transposed per cell)."""
 
-    def __init__(self, lv, k, nu, beta, gamma, winds=None, dirichlet=None):
+    def __init__(self, lv, k, nu, beta, gamma, winds=None, dirichlet=None, transpose=False):
         super().__init__(lv, k, nu, beta, gamma)
         if winds is not None:
-            self.elems = [OseenElement(e, convection_matrix(e, winds[K]))
-                          for K, e in enumerate(self.elems)]
+            def conv(e, K):
+                C = convection_matrix(e, winds[K])
+                return C.T.copy() if transpose else C
+            self.elems = [OseenElement(e, conv(e, K)) for K, e in enumerate(self.elems)]
         self.dirichlet = dirichlet
 
     def boundary_local(self, K):
@@ -233,7 +242,7 @@ class OseenHierarchy(mg.Hierarchy):
     """Lowest-order levels with the convection of the RT0-projected wind
     (flux: facet fluxes of the wind on the finest level; None: Stokes)."""
 
-    def __init__(self, levels, nu_fine, beta, eps_inv, flux=None, harmonic=True):
+    def __init__(self, levels, nu_fine, beta, eps_inv, flux=None, harmonic=True, transpose=False):
         self.levels = levels
         J = len(levels)
         nus = [None] * J
@@ -250,7 +259,7 @@ class OseenHierarchy(mg.Hierarchy):
         self.A = []
         for l, lv in enumerate(levels):
             winds = None if flux is None else rt0_winds(lv, fluxes[l])
-            pr = OseenProblem(lv, 0, nus[l], beta, eps_inv, winds)
+            pr = OseenProblem(lv, 0, nus[l], beta, eps_inv, winds, transpose=transpose)
             self.A.append(pr.matrix_Aeps().tocsr())
         self.smooth = [None] + [mg.PatchGS(self.A[l], levels[l], 1) for l in range(1, J)]
         self.P, self.R = [None], [None]
@@ -344,16 +353,17 @@ class OseenSetup:
     Oseen hierarchy."""
 
     def __init__(self, levels, k, nu, beta, gamma, winds=None, dirichlet=None, m_p=1, m_h=1,
-                 q=1, growth=2, restart=50):
+                 q=1, growth=2, restart=50, transpose=False):
         self.levels = levels
         self.lv = levels[-1]
         self.k = k
-        self.prob = OseenProblem(self.lv, k, nu, beta, gamma, winds, dirichlet)
+        self.prob = OseenProblem(self.lv, k, nu, beta, gamma, winds, dirichlet, transpose)
         self.Aeps = self.prob.matrix_Aeps().tocsr()
         self.D = self.prob.matrix_D().tocsr()
         self.eps_inv = self.prob.eps_inv
         flux = None if winds is None else facet_fluxes(self.lv, winds)
-        self.hier = OseenHierarchy(levels, self.prob.nu_c, beta, self.eps_inv, flux)
+        self.hier = OseenHierarchy(levels, self.prob.nu_c, beta, self.eps_inv, flux,
+                                   transpose=transpose)
         self.prec = mg.HPMG(self.Aeps, self.lv, k, self.hier, m_p, m_h, q, growth)
         self.restart = restart
 

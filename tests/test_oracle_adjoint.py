@@ -105,3 +105,133 @@ def test_method_adjoint_reaches_dense_adjoint():
     assert abs(J1 - J0) <= 1e-8 * abs(J0)
     assert np.abs(gf1 - gf0).max() <= 1e-7 * np.abs(gf0).max()
     assert np.abs(gnu1 - gnu0).max() <= 1e-7 * np.abs(gnu0).max()
+
+
+# ---------------------------------------------------------------- Oseen
+# The Picard-linearised system at a fixed wind is nonsymmetric; its adjoint
+# is the transposed system (oracle.oseen, transpose=True).  The pins below
+# check the transposed condensation against the forward one and the
+# gradients against finite differences, the linear-response identity and
+# the method's FGMRES solve of the transposed system.
+from oracle import oseen  # noqa: E402
+
+_OSEEN = {}
+
+
+def oseen_case(k, n=2, n_refine=1, scale=20.0, beta=1.0):
+    key = (k, n, n_refine, scale, beta)
+    if key in _OSEEN:
+        return _OSEEN[key]
+    c, t = synth.kuhn_square(n)
+    levels = mesh.hierarchy(c, t, n_refine)
+    lv = levels[-1]
+    nq = (k + 2) ** 2
+    nu = 0.1 * np.exp(0.5 * synth.normal(3, 0, lv.n_cells))
+    pr0 = hdg.Problem(lv, k, 1.0, 1.0, 1e2)
+    f0 = synth.source_uniform(100, 1, lv.n_cells, nq)[0]
+    lam0, p00 = pr0.solve_direct(f0)
+    winds = [(lambda X, w=w: scale * w(X)) for w in oseen.state_wind(pr0, lam0, p00, f0)]
+    f = synth.source_uniform(7, 1, lv.n_cells, nq)[0]
+    ut = synth.source_uniform(4, 1, lv.n_cells, nq)[0]
+    _OSEEN[key] = (levels, lv, nu, beta, winds, f, ut)
+    return _OSEEN[key]
+
+
+def oseen_misfit(lv, k, nu, beta, winds, f, ut):
+    pr = oseen.OseenProblem(lv, k, nu, beta, 1e2, winds)
+    lam, p0 = pr.solve_direct(f)
+    return adjoint.misfit(pr, adjoint.velocity(pr, lam, p0, f), ut)
+
+
+def oseen_gradients(k, **kw):
+    levels, lv, nu, beta, winds, f, ut = oseen_case(k, **kw)
+    fwd = oseen.OseenProblem(lv, k, nu, beta, 1e2, winds)
+    adj = oseen.OseenProblem(lv, k, nu, beta, 1e2, winds, transpose=True)
+    return fwd, adj, adjoint.gradients(fwd, f, ut, prob_adj=adj)
+
+
+@pytest.mark.parametrize("k", [0, 2])
+def test_oseen_transposed_condensation(k):
+    # Condensation commutes with transposition: each cell block of the
+    # transposed system is the transpose of the forward block, and both are
+    # far from symmetric (the wind is strong).
+    levels, lv, nu, beta, winds, f, ut = oseen_case(k)
+    fwd = oseen.OseenProblem(lv, k, nu, beta, 1e2, winds)
+    adj = oseen.OseenProblem(lv, k, nu, beta, 1e2, winds, transpose=True)
+    for ef, ea in zip(fwd.elems, adj.elems):
+        assert np.abs(ea.S - ef.S.T).max() <= 1e-12 * np.abs(ef.S).max()
+    A, At = fwd.matrix_Aeps().toarray(), adj.matrix_Aeps().toarray()
+    assert np.abs(At - A.T).max() <= 1e-12 * np.abs(A).max()
+    A0 = fwd.matrix_A().toarray()  # without the (symmetric) AL term
+    assert np.abs(A - A.T).max() >= 1e-3 * np.abs(A0).max()
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_oseen_grad_nu_matches_central_differences(k):
+    levels, lv, nu, beta, winds, f, ut = oseen_case(k)
+    _, _, (J, gf, gnu, _) = oseen_gradients(k)
+    h = 1e-4
+    for K in (0, 7, lv.n_cells - 1):
+        e = np.zeros(lv.n_cells)
+        e[K] = h * nu[K]
+        fd = (oseen_misfit(lv, k, nu + e, beta, winds, f, ut) -
+              oseen_misfit(lv, k, nu - e, beta, winds, f, ut)) / (2 * e[K])
+        assert abs(fd - gnu[K]) <= 1e-6 * np.abs(gnu).max(), (K, fd, gnu[K])
+
+
+def test_oseen_grad_f_matches_central_differences_and_needs_the_transpose():
+    k = 1
+    levels, lv, nu, beta, winds, f, ut = oseen_case(k)
+    fwd, adj, (J, gf, gnu, _) = oseen_gradients(k)
+    # the forward system's own solve in place of the transposed one gives a
+    # visibly different gradient: the pin below can tell them apart
+    _, gf_wrong, _, _ = adjoint.gradients(fwd, f, ut)
+    assert np.abs(gf_wrong - gf).max() >= 1e-2 * np.abs(gf).max()
+    rng = np.random.default_rng(1)
+    h = 1e-4  # J is quadratic in f: central differences are exact up to rounding
+    for _ in range(6):
+        K, q, i = rng.integers(lv.n_cells), rng.integers(f.shape[1]), rng.integers(2)
+        fp, fm = f.copy(), f.copy()
+        fp[K, q, i] += h
+        fm[K, q, i] -= h
+        fd = (oseen_misfit(lv, k, nu, beta, winds, fp, ut) -
+              oseen_misfit(lv, k, nu, beta, winds, fm, ut)) / (2 * h)
+        assert abs(fd - gf[K, q, i]) <= 1e-8 * np.abs(gf).max() + 1e-12
+
+
+def test_oseen_grad_f_is_linear_response_transpose():
+    k = 2
+    levels, lv, nu, beta, winds, f, ut = oseen_case(k)
+    fwd, adj, (J, gf, gnu, _) = oseen_gradients(k)
+    lam, p0 = fwd.solve_direct(f)
+    gu = adjoint.misfit_grad(fwd, adjoint.velocity(fwd, lam, p0, f), ut)
+    for s in range(3):
+        df = synth.source_uniform(50 + s, 1, lv.n_cells, f.shape[1])[0]
+        l2, p2 = fwd.solve_direct(df)
+        du = adjoint.velocity(fwd, l2, p2, df)
+        assert abs(np.sum(gu * du) - np.sum(gf * df)) <= 1e-10 * np.abs(gf).sum()
+
+
+def test_oseen_method_adjoint_reaches_dense_adjoint():
+    # the method on the transposed system: AL-Uzawa + FGMRES preconditioned
+    # by MG_hp built from the transposed blocks (patch factors, harmonic
+    # transfers and lowest-order wind blocks all of A^T)
+    k = 2
+    levels, lv, nu, beta, winds, f, ut = oseen_case(k, n_refine=2)
+    fwd, adj, (J0, gf0, gnu0, _) = oseen_gradients(k, n_refine=2)
+    Sf = oseen.OseenSetup(levels, k, nu, beta, 1e2, winds)
+    Sa = oseen.OseenSetup(levels, k, nu, beta, 1e2, winds, transpose=True)
+
+    def method(S):
+        def run(fq):
+            r = S.solve(fq)
+            run.its = r["its"]
+            return r["lam"], r["p0"]
+        return run
+
+    sa = method(Sa)
+    J1, gf1, gnu1, _ = adjoint.gradients(Sf.prob, f, ut, solve=method(Sf), prob_adj=Sa.prob, solve_adj=sa)
+    assert abs(J1 - J0) <= 1e-8 * abs(J0)
+    assert np.abs(gf1 - gf0).max() <= 1e-7 * np.abs(gf0).max()
+    assert np.abs(gnu1 - gnu0).max() <= 1e-7 * np.abs(gnu0).max()
+    assert max(sa.its) <= 60, sa.its
