@@ -113,11 +113,19 @@ typedef struct {
                               preconditioning; 0: generalized Stokes with
                               flexible CG                                   */
   int restart;             /* FGMRES restart length, 1..64                  */
+  int transpose;           /* 1 (with oseen = 1): the context assembles and
+                              solves the transposed system A^T of the
+                              Picard-linearised scheme at the wind it is
+                              given (every cell's convection form
+                              transposed; blocks, patch factors, transfers
+                              and the coarsest inverse are then those of
+                              A^T): the adjoint of the Oseen system, used
+                              by hdgmg_solve_adjoint; 0: the system itself */
 } hdgmg_opts;
 
 /* Defaults: m_p = m_h = 1, V-cycle, growth 2, rtol 1e-8, atol 1e-10,
  * max_it 500, uzawa_max 50, uzawa_tol 1e-10, coarse_dofs 2048,
- * stream_dofs 65536, vcycle_precision 0, oseen 0, restart 50. */
+ * stream_dofs 65536, vcycle_precision 0, oseen 0, restart 50, transpose 0. */
 void hdgmg_default_opts(hdgmg_opts* opts);
 
 #define HDGMG_MAX_UZAWA 64
@@ -170,7 +178,9 @@ hdgmg_status hdgmg_solve(hdgmg_ctx* ctx, const double* f_qp, double* u_qp,
 /* Adjoint solve for a functional J(u_qp) of the velocity at the data points
  * (not in the paper; derived from the scheme of Sec. 3.2, whose system is a
  * symmetric saddle point in which the viscosity enters only through the
- * nu-weighted lifting energy of each cell).
+ * nu-weighted lifting energy of each cell, and from its Picard-linearised
+ * form of Sec. 4.2 at a fixed wind, whose convection form is nonsymmetric
+ * and independent of the viscosity).
  *   f_qp   device [n_cells][n_q][2], input: the forward source
  *   state  device [N_skel + n_cells], input: the forward state written by
  *          hdgmg_solve for f_qp (the forward solution is checkpointed as
@@ -182,11 +192,20 @@ hdgmg_status hdgmg_solve(hdgmg_ctx* ctx, const double* f_qp, double* u_qp,
  *          gnu[K] += dJ/dnu_K = -(Lift(u, uhat), Lift(u_adj, uhat_adj))_K
  *   adj_state device [N_skel + n_cells], output, may be NULL: the adjoint state
  *   info   host, may be NULL: the adjoint solve's Uzawa / inner iterations
- * The adjoint state solves the forward system (same AL-Uzawa, flexible CG
- * and MG_hp) with the load v -> sum_{K,q} gu_qp . v(x_q).  gf_qp must not
- * alias the inputs.  Returns as hdgmg_solve; outputs are undefined on a
- * negative status.  ESTATE while a wind or Dirichlet data are set (the
- * adjoint of the nonsymmetric and inhomogeneous cases is not provided). */
+ * The adjoint state solves the transposed system with the load
+ * v -> sum_{K,q} gu_qp . v(x_q): for generalized Stokes (symmetric) the
+ * forward system itself (same AL-Uzawa, flexible CG and MG_hp); for the
+ * Oseen system at a wind, the context must have been set up with
+ * opts.oseen = 1 and opts.transpose = 1 and given the forward wind
+ * (hdgmg_set_wind, hdgmg_assemble): it then holds A^T, the adjoint state
+ * is its AL-Uzawa + FGMRES solve preconditioned by MG_hp of A^T, and in
+ * gnu the forward state's local fields are recovered with the forward
+ * cell systems and the adjoint's with the transposed ones.  state must
+ * come from a context with the same mesh, order, coefficients and wind.
+ * gf_qp must not alias the inputs.  Returns as hdgmg_solve; outputs are
+ * undefined on a negative status.  ESTATE while Dirichlet data are set, or
+ * with a wind on a context without opts.transpose (the adjoint of the
+ * inhomogeneous case is not provided). */
 hdgmg_status hdgmg_solve_adjoint(hdgmg_ctx* ctx, const double* f_qp, const double* state,
                                  const double* gu_qp, double* gf_qp, double* gnu,
                                  double* adj_state, hdgmg_info* info);

@@ -217,6 +217,19 @@ __global__ void __launch_bounds__(WL) k_condense_wave(ElemLevel E, double* __res
     }
   }
 
+  // ---- transposed (adjoint) cell: H <- H^T (only the convection part is
+  // nonsymmetric); one lane per pair
+  if (conv && E.transpose) {
+    for (int e = lane; e < nz * nz; e += WL) {
+      const int a = e / nz, b = e % nz;
+      if (b < a) {
+        const double t = H[(long)a * nz + b];
+        H[(long)a * nz + b] = H[(long)b * nz + a];
+        H[(long)b * nz + a] = t;
+      }
+    }
+    __syncthreads();
+  }
   // ---- H += nu sum_ij R_ij^T M^-1 R_ij (Cholesky of M on one lane)
   if (lane == 0) {
     for (int j = 0; j < nP; ++j) {

@@ -258,12 +258,17 @@ enum { EL_CONDENSE = 0, EL_LOAD = 1, EL_RECOVER = 2, EL_GRADNU = 3 };
 // the volume terms then use the convection rule and the source term the
 // data rule.  H is nonsymmetric; rows are test functions, so the condensed
 // rows of tangential unknowns read H_ta (rows), not H_at^T, and S is not
-// symmetrised.
+// symmetrised.  transpose: the cell of the transposed (adjoint) system, H
+// replaced by H^T before the local solve (only the convection part is
+// nonsymmetric); the condensed block is then S^T and the load, recovery and
+// kept factors are those of the transposed local system.  EL_GRADNU ignores
+// it: with a wind it recovers (f, lam) with the forward local system and
+// (f2, lam2) with the transposed one (the forward and adjoint states).
 HDI int element_local(const QuadTables& Q, const CellGeom& g, double nu, double beta,
                       double eps_inv, int mode, const double* f, const double* lam,
                       double p0, WS w, double* out, const double* f2 = nullptr,
                       const double* lam2 = nullptr, const ConvTables* CT = nullptr,
-                      const double* wc = nullptr, const WS* fac = nullptr) {
+                      const double* wc = nullptr, const WS* fac = nullptr, bool transpose = false) {
   const Dims D = dims_of(Q.k);
   const int nP = D.nP, na = D.na, nz = D.nz, m = D.m, nK = D.nK, nN = D.nN, nkkt = D.nkkt;
   long o = 0;
@@ -336,6 +341,8 @@ HDI int element_local(const QuadTables& Q, const CellGeom& g, double nu, double 
         double wt = Q.wq[q] * g.area;
         rt_basis(D, g, x1, x2, xp, u, gr, mono);
         for (int a = 0; a < na; ++a) F[a] += wt * (f[2 * q] * u[2 * a] + f[2 * q + 1] * u[2 * a + 1]);
+        if (mode == EL_GRADNU)
+          for (int a = 0; a < na; ++a) F[na + a] += wt * (f2[2 * q] * u[2 * a] + f2[2 * q + 1] * u[2 * a + 1]);
       }
     // - sum_ij (u_i w_j, d_j v_i): H[test b][trial a]
     for (int q = 0; q < CT->nq; ++q) {
@@ -424,6 +431,15 @@ HDI int element_local(const QuadTables& Q, const CellGeom& g, double nu, double 
       }
     }
   }
+  if (conv && transpose && mode != EL_GRADNU)
+    for (int a = 0; a < nz; ++a)
+      for (int b = 0; b < a; ++b) {
+        const double t = H[(long)a * nz + b];
+        H[(long)a * nz + b] = H[(long)b * nz + a];
+        H[(long)b * nz + a] = t;
+      }
+  // the second state of EL_GRADNU is solved with the transposed local system
+  const bool tcol = conv && mode == EL_GRADNU;
   // ---- H += nu sum_ij R_ij^T M^-1 R_ij (Cholesky of M)
   for (int j = 0; j < nP; ++j) {
     double d = M[j * nP + j];
@@ -523,12 +539,41 @@ HDI int element_local(const QuadTables& Q, const CellGeom& g, double nu, double 
     if (mode == EL_RECOVER || mode == EL_GRADNU) {
       for (int cc = 0; cc < ncol; ++cc) {
         const double* lm = cc == 0 ? lam : lam2;
+        const bool tr = tcol && cc == 1;  // H^T: coupling H[t][a] in place of H[a][t]
         for (int i = 0; i < 3; ++i)
           for (int j = 0; j < m; ++j) {
             double cn = lm[(i * 2 + 0) * m + j], ct = lm[(i * 2 + 1) * m + j];
             Bx[(long)(na + i * m + j) * ncol + cc] += cn;
-            for (int a = 0; a < na; ++a) Bx[(long)a * ncol + cc] -= H[(long)a * nz + na + i * m + j] * ct;
+            const long tt = na + i * m + j;
+            for (int a = 0; a < na; ++a)
+              Bx[(long)a * ncol + cc] -= (tr ? H[tt * nz + a] : H[(long)a * nz + tt]) * ct;
           }
+      }
+    }
+  }
+  // The factors satisfy P KKT = L U (P: the row interchanges j <-> piv[j]
+  // in order j = 0, 1, ...).  A transposed column solves
+  // KKT^T x = U^T L^T P x = b: U^T z = b, L^T w = z, x = P^T w (the
+  // interchanges undone in reverse order).
+  const int ncol_fwd = tcol ? 1 : ncol;
+  if (tcol) {
+    const int c = 1;
+    for (int i = 0; i < nkkt; ++i) {
+      double s = Bx[(long)i * ncol + c];
+      for (int p = 0; p < i; ++p) s -= Kk[(long)p * nkkt + i] * Bx[(long)p * ncol + c];
+      Bx[(long)i * ncol + c] = s / Kk[(long)i * nkkt + i];
+    }
+    for (int i = nkkt - 1; i >= 0; --i) {
+      double s = Bx[(long)i * ncol + c];
+      for (int p = i + 1; p < nkkt; ++p) s -= Kk[(long)p * nkkt + i] * Bx[(long)p * ncol + c];
+      Bx[(long)i * ncol + c] = s;
+    }
+    for (int j = nkkt - 1; j >= 0; --j) {
+      int pr = (int)piv[j];
+      if (pr != j) {
+        double t = Bx[(long)j * ncol + c];
+        Bx[(long)j * ncol + c] = Bx[(long)pr * ncol + c];
+        Bx[(long)pr * ncol + c] = t;
       }
     }
   }
@@ -536,13 +581,13 @@ HDI int element_local(const QuadTables& Q, const CellGeom& g, double nu, double 
   for (int j = 0; j < nkkt; ++j) {
     int pr = (int)piv[j];
     if (pr != j)
-      for (int c = 0; c < ncol; ++c) {
+      for (int c = 0; c < ncol_fwd; ++c) {
         double t = Bx[(long)j * ncol + c];
         Bx[(long)j * ncol + c] = Bx[(long)pr * ncol + c];
         Bx[(long)pr * ncol + c] = t;
       }
   }
-  for (int c = 0; c < ncol; ++c) {
+  for (int c = 0; c < ncol_fwd; ++c) {
     for (int i = 0; i < nkkt; ++i) {
       double s = Bx[(long)i * ncol + c];
       for (int p = 0; p < i; ++p) s -= Kk[(long)i * nkkt + p] * Bx[(long)p * ncol + c];

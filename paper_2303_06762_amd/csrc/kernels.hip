@@ -24,7 +24,7 @@ __global__ void k_condense(ElemLevel E, int c0, int nbatch, double* ws, double* 
   const WS fv{E.fac ? E.fac + c : nullptr, E.nc};
   int rc = element_local(E.Q, g, nuc, E.beta, E.eps_inv, EL_CONDENSE, nullptr, nullptr, 0.0, WS{ws + t, nbatch},
                          S + (long)c * nK * nK, nullptr, nullptr, E.CT, E.wcoef ? E.wcoef + (long)c * E.na : nullptr,
-                         E.fac ? &fv : nullptr);
+                         E.fac ? &fv : nullptr, E.transpose != 0);
   if (rc) atomicOr(status, 1);
 }
 
@@ -53,7 +53,7 @@ __global__ void k_load(ElemLevel E, int c0, int nbatch, const double* __restrict
   } else {
     int rc = element_local(E.Q, g, nuc, E.beta, 0.0, EL_LOAD, f + (long)c * E.Q.nq * 2, nullptr, 0.0,
                            WS{ws + t, nbatch}, out, nullptr, nullptr, E.CT,
-                           E.wcoef ? E.wcoef + (long)c * E.na : nullptr);
+                           E.wcoef ? E.wcoef + (long)c * E.na : nullptr, nullptr, E.transpose != 0);
     if (rc) atomicOr(status, 1);
   }
   if (E.bdl) {
@@ -93,7 +93,7 @@ __global__ void k_recover(ElemLevel E, int c0, int nbatch, const double* __restr
   } else {
     int rc = element_local(E.Q, g, nuc, E.beta, 0.0, EL_RECOVER, f + (long)c * E.Q.nq * 2, lk, p0[c],
                            WS{ws + t, nbatch}, out, nullptr, nullptr, E.CT,
-                           E.wcoef ? E.wcoef + (long)c * E.na : nullptr);
+                           E.wcoef ? E.wcoef + (long)c * E.na : nullptr, nullptr, E.transpose != 0);
     if (rc) atomicOr(status, 1);
   }
   for (int q = 0; q < E.Q.nq; ++q) {
@@ -183,20 +183,21 @@ __global__ void k_bd_local(int nc, int m, const int* __restrict__ cbf, const dou
 }
 
 // gnu[c] += -(Lift z, Lift z_adj)_K for the forward state (f, lam) and the
-// adjoint state (fa, lama) of every cell of the batch.
-__global__ void k_gradnu(QuadTables Q, const double* __restrict__ X, const int* __restrict__ cells,
-                         int c0, int nbatch, const double* __restrict__ nu, int nu_per_cell, double beta,
-                         const double* __restrict__ f, const double* __restrict__ lam,
-                         const double* __restrict__ fa, const double* __restrict__ lama, int m,
-                         const int* __restrict__ cell_dofs, double* ws, double* gnu, int* status) {
+// adjoint state (fa, lama) of every cell of the batch.  With a wind the
+// forward state is recovered with the cell's own local system and the
+// adjoint state with its transpose.
+__global__ void k_gradnu(ElemLevel E, int c0, int nbatch, const double* __restrict__ f,
+                         const double* __restrict__ lam, const double* __restrict__ fa,
+                         const double* __restrict__ lama, double* ws, double* gnu, int* status) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nbatch) return;
   int c = c0 + t;
+  const int m = E.m;
   CellGeom g;
-  cell_geom(X, cells + 3 * c, g);
+  cell_geom(E.X, E.cells + 3 * c, g);
   double lk[6 * (KMAX + 1)], la[6 * (KMAX + 1)];
   for (int i = 0; i < 3; ++i) {
-    int d = cell_dofs[3 * c + i];
+    int d = E.cell_dofs[3 * c + i];
     for (int cc = 0; cc < 2; ++cc)
       for (int j = 0; j < m; ++j) {
         const long gi = ((long)d * 2 + cc) * m + j;
@@ -205,9 +206,10 @@ __global__ void k_gradnu(QuadTables Q, const double* __restrict__ X, const int* 
       }
   }
   double out[1];
-  double nuc = nu_per_cell ? nu[c] : nu[0];
-  int rc = element_local(Q, g, nuc, beta, 0.0, EL_GRADNU, f + (long)c * Q.nq * 2, lk, 0.0, WS{ws + t, nbatch},
-                         out, fa + (long)c * Q.nq * 2, la);
+  double nuc = E.nu_per_cell ? E.nu[c] : E.nu[0];
+  int rc = element_local(E.Q, g, nuc, E.beta, 0.0, EL_GRADNU, f + (long)c * E.Q.nq * 2, lk, 0.0,
+                         WS{ws + t, nbatch}, out, fa + (long)c * E.Q.nq * 2, la, E.CT,
+                         E.wcoef ? E.wcoef + (long)c * E.na : nullptr);
   if (rc) atomicOr(status, 1);
   gnu[c] += out[0];
 }
@@ -769,12 +771,10 @@ void launch_bd_local(hipStream_t st, int nc, int m, const int* cbf, const double
   const long n = (long)nc * 3 * m;
   if (n > 0) hipLaunchKernelGGL(k_bd_local, dim3(nblk(n)), dim3(TPB), 0, st, nc, m, cbf, uhat_b, bdl);
 }
-void launch_gradnu(hipStream_t st, const QuadTables& Q, const double* X, const int* cells, int c0, int nbatch,
-                   const double* nu, int nu_per_cell, double beta, const double* f, const double* lam,
-                   const double* fa, const double* lama, int m, const int* cell_dofs, double* ws, double* gnu,
-                   int* status) {
-  hipLaunchKernelGGL(k_gradnu, dim3(nblk(nbatch, 64)), dim3(64), 0, st, Q, X, cells, c0, nbatch, nu,
-                     nu_per_cell, beta, f, lam, fa, lama, m, cell_dofs, ws, gnu, status);
+void launch_gradnu(hipStream_t st, const ElemLevel& E, int c0, int nbatch, const double* f, const double* lam,
+                   const double* fa, const double* lama, double* ws, double* gnu, int* status) {
+  hipLaunchKernelGGL(k_gradnu, dim3(nblk(nbatch, 64)), dim3(64), 0, st, E, c0, nbatch, f, lam, fa, lama, ws, gnu,
+                     status);
 }
 void launch_data_weight(hipStream_t st, const QuadTables& Q, const double* X, const int* cells, int nc,
                         const double* in, int inverse, double* out) {

@@ -45,6 +45,7 @@ struct ElemLevel {
   double* fac;              // kept local factors (element_fac_size per cell, element i
                             // of cell c at fac[i * nc + c]), or null
   int nc;
+  int transpose;            // 1: cells of the transposed (adjoint) system (with a wind)
 };
 
 void launch_condense(hipStream_t st, const ElemLevel& E, int c0, int nbatch, double* ws, double* S, int* status);
@@ -73,10 +74,8 @@ void launch_facet_flux(hipStream_t st, const QuadTables& Q, const double* X, con
 void launch_bd_local(hipStream_t st, int nc, int m, const int* cbf, const double* uhat_b, double* bdl);
 // gnu[c] += -(Lift z, Lift z_adj)_K for cells c0 .. c0+nbatch (forward
 // source f and skeleton vector lam, adjoint source fa and skeleton vector lama).
-void launch_gradnu(hipStream_t st, const QuadTables& Q, const double* X, const int* cells, int c0, int nbatch,
-                   const double* nu, int nu_per_cell, double beta, const double* f, const double* lam,
-                   const double* fa, const double* lama, int m, const int* cell_dofs, double* ws, double* gnu,
-                   int* status);
+void launch_gradnu(hipStream_t st, const ElemLevel& E, int c0, int nbatch, const double* f, const double* lam,
+                   const double* fa, const double* lama, double* ws, double* gnu, int* status);
 // out = in * (w_q |K|), or in / (w_q |K|) when inverse != 0, on [nc][nq][2].
 void launch_data_weight(hipStream_t st, const QuadTables& Q, const double* X, const int* cells, int nc,
                         const double* in, int inverse, double* out);

@@ -1267,6 +1267,7 @@ ElemLevel elem_level(const hdgmg_ctx* ctx, const DevLevel& D, bool order_k, bool
   E.S = D.S;
   E.fac = order_k ? ctx->fac : nullptr;
   E.nc = D.nc;
+  E.transpose = E.CT && ctx->opts.transpose ? 1 : 0;
   return E;
 }
 
@@ -1290,8 +1291,7 @@ hdgmg_status batched(hdgmg_ctx* ctx, DevLevel& D, const ElemLevel& E, int mode, 
     else if (mode == EL_LOAD)
       launch_load(ctx->st, E, (int)c0, nb, f, ctx->ws, out1, ctx->status);
     else if (mode == EL_GRADNU)
-      launch_gradnu(ctx->st, E.Q, D.X, D.cells, (int)c0, nb, D.nu, 1, ctx->beta, f, lam, f2, lam2, D.m,
-                    D.cell_dofs, ctx->ws, out1, ctx->status);
+      launch_gradnu(ctx->st, E, (int)c0, nb, f, lam, f2, lam2, ctx->ws, out1, ctx->status);
     else
       launch_recover(ctx->st, E, (int)c0, nb, f, lam, p0, ctx->ws, out1, out2, ctx->status);
     HIPC(hipGetLastError());
@@ -1361,6 +1361,7 @@ void hdgmg_default_opts(hdgmg_opts* o) {
   o->vcycle_precision = 0;
   o->oseen = 0;
   o->restart = 50;
+  o->transpose = 0;
 }
 
 const char* hdgmg_last_error(const hdgmg_ctx* ctx) {
@@ -1414,7 +1415,8 @@ hdgmg_status hdgmg_setup(const hdgmg_mesh* mesh, int k, double beta, const doubl
       ctx->opts.vcycle_growth < 1 || ctx->opts.max_it < 1 || ctx->opts.uzawa_max < 1 ||
       ctx->opts.uzawa_max > HDGMG_MAX_UZAWA || !(ctx->opts.rtol >= 0) || !(ctx->opts.atol >= 0) ||
       ctx->opts.vcycle_precision < 0 || ctx->opts.vcycle_precision > 2 || ctx->opts.oseen < 0 ||
-      ctx->opts.oseen > 1 || ctx->opts.restart < 1 || ctx->opts.restart > 64) {
+      ctx->opts.oseen > 1 || ctx->opts.restart < 1 || ctx->opts.restart > 64 || ctx->opts.transpose < 0 ||
+      ctx->opts.transpose > 1 || (ctx->opts.transpose && !ctx->opts.oseen)) {
     g_setup_error = "invalid options";
     delete ctx;
     return HDGMG_EINVAL;
@@ -1836,8 +1838,12 @@ hdgmg_status hdgmg_solve_adjoint(hdgmg_ctx* ctx, const double* f_qp, const doubl
     ctx->err = "hdgmg_solve_adjoint before hdgmg_assemble";
     return HDGMG_ESTATE;
   }
-  if (ctx->has_wind || ctx->has_bd) {
-    ctx->err = "hdgmg_solve_adjoint with a wind or Dirichlet data is not provided";
+  if (ctx->has_bd) {
+    ctx->err = "hdgmg_solve_adjoint with Dirichlet data is not provided";
+    return HDGMG_ESTATE;
+  }
+  if (ctx->has_wind && !ctx->opts.transpose) {
+    ctx->err = "the adjoint of an Oseen system needs a context set up with opts.transpose = 1";
     return HDGMG_ESTATE;
   }
   const DevLevel& KL = ctx->K;
@@ -1857,7 +1863,7 @@ hdgmg_status hdgmg_solve_adjoint(hdgmg_ctx* ctx, const double* f_qp, const doubl
   launch_data_weight(ctx->st, ctx->Q, KL.X, KL.cells, KL.nc, gf_qp, 0, gf_qp);
   HIPC(hipGetLastError());
   if (gnu)
-    TRY(batched(ctx, ctx->K, elem_level(ctx, ctx->K, true, false), EL_GRADNU, f_qp, state, nullptr, gnu, nullptr,
+    TRY(batched(ctx, ctx->K, elem_level(ctx, ctx->K, true, true), EL_GRADNU, f_qp, state, nullptr, gnu, nullptr,
                 ctx->adj_f, ast));
   HIPC(hipStreamSynchronize(ctx->st));
   return result;
