@@ -202,10 +202,12 @@ hdgmg_status hdgmg_solve(hdgmg_ctx* ctx, const double* f_qp, double* u_qp,
  * gnu the forward state's local fields are recovered with the forward
  * cell systems and the adjoint's with the transposed ones.  state must
  * come from a context with the same mesh, order, coefficients and wind.
- * gf_qp must not alias the inputs.  Returns as hdgmg_solve; outputs are
- * undefined on a negative status.  ESTATE while Dirichlet data are set, or
- * with a wind on a context without opts.transpose (the adjoint of the
- * inhomogeneous case is not provided). */
+ * Tangential Dirichlet data set on the context (hdgmg_set_dirichlet; on an
+ * adjoint context, the forward context's values) are the forward state's:
+ * the adjoint state has homogeneous data, and the values enter only the
+ * forward local fields of gnu.  gf_qp must not alias the inputs.  Returns
+ * as hdgmg_solve; outputs are undefined on a negative status.  ESTATE with a
+ * wind on a context without opts.transpose. */
 hdgmg_status hdgmg_solve_adjoint(hdgmg_ctx* ctx, const double* f_qp, const double* state,
                                  const double* gu_qp, double* gf_qp, double* gnu,
                                  double* adj_state, hdgmg_info* info);

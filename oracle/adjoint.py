@@ -28,6 +28,12 @@ unchanged) with the same load functional.  The two formulas above keep
 their form, with the adjoint's local fields recovered by the transposed
 local solve: dJ/dnu_K = -(Lift(z), Lift(z_adj))_K still holds because the
 convection form does not depend on nu.
+
+Inhomogeneous tangential Dirichlet data (the lid of the cavity) enter the
+forward load and the forward local fields only: the adjoint state has
+homogeneous data (its test space is the forward's), so prob_adj is then the
+same system without the boundary values, while the forward state's lifting
+in dJ/dnu keeps them.
 """
 import numpy as np
 
@@ -80,8 +86,9 @@ def gradients(prob, f_qp, ut_qp, solve=None, prob_adj=None, solve_adj=None):
 
     solve(f_qp) -> (lam, p0) defaults to the direct solve of the condensed
     saddle point (the dense adjoint); the method's solve can be passed in.
-    prob_adj / solve_adj: the transposed system and its solve, for
-    nonsymmetric (Oseen) problems; by default the forward ones."""
+    prob_adj / solve_adj: the transposed system with homogeneous boundary
+    data and its solve, for nonsymmetric (Oseen) problems or inhomogeneous
+    Dirichlet data; by default the forward ones."""
     solve = solve or prob.solve_direct
     pa = prob_adj or prob
     solve_adj = solve_adj or (pa.solve_direct if prob_adj is not None else solve)

@@ -185,7 +185,8 @@ __global__ void k_bd_local(int nc, int m, const int* __restrict__ cbf, const dou
 // gnu[c] += -(Lift z, Lift z_adj)_K for the forward state (f, lam) and the
 // adjoint state (fa, lama) of every cell of the batch.  With a wind the
 // forward state is recovered with the cell's own local system and the
-// adjoint state with its transpose.
+// adjoint state with its transpose; prescribed boundary values (E.bdl)
+// belong to the forward state only (the adjoint's are zero).
 __global__ void k_gradnu(ElemLevel E, int c0, int nbatch, const double* __restrict__ f,
                          const double* __restrict__ lam, const double* __restrict__ fa,
                          const double* __restrict__ lama, double* ws, double* gnu, int* status) {
@@ -196,13 +197,16 @@ __global__ void k_gradnu(ElemLevel E, int c0, int nbatch, const double* __restri
   CellGeom g;
   cell_geom(E.X, E.cells + 3 * c, g);
   double lk[6 * (KMAX + 1)], la[6 * (KMAX + 1)];
+  boundary_local(E, c, lk);
+  for (int i = 0; i < 6 * m; ++i) la[i] = 0.0;
   for (int i = 0; i < 3; ++i) {
     int d = E.cell_dofs[3 * c + i];
+    if (d < 0) continue;
     for (int cc = 0; cc < 2; ++cc)
       for (int j = 0; j < m; ++j) {
         const long gi = ((long)d * 2 + cc) * m + j;
-        lk[(i * 2 + cc) * m + j] = d >= 0 ? lam[gi] : 0.0;
-        la[(i * 2 + cc) * m + j] = d >= 0 ? lama[gi] : 0.0;
+        lk[(i * 2 + cc) * m + j] = lam[gi];
+        la[(i * 2 + cc) * m + j] = lama[gi];
       }
   }
   double out[1];

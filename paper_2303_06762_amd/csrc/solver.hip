@@ -1838,10 +1838,6 @@ hdgmg_status hdgmg_solve_adjoint(hdgmg_ctx* ctx, const double* f_qp, const doubl
     ctx->err = "hdgmg_solve_adjoint before hdgmg_assemble";
     return HDGMG_ESTATE;
   }
-  if (ctx->has_bd) {
-    ctx->err = "hdgmg_solve_adjoint with Dirichlet data is not provided";
-    return HDGMG_ESTATE;
-  }
   if (ctx->has_wind && !ctx->opts.transpose) {
     ctx->err = "the adjoint of an Oseen system needs a context set up with opts.transpose = 1";
     return HDGMG_ESTATE;
@@ -1857,7 +1853,12 @@ hdgmg_status hdgmg_solve_adjoint(hdgmg_ctx* ctx, const double* f_qp, const doubl
   // the adjoint load v -> sum gu . v(x_q) is the forward load of gu / (w_q |K|)
   launch_data_weight(ctx->st, ctx->Q, KL.X, KL.cells, KL.nc, gu_qp, 1, ctx->adj_f);
   HIPC(hipGetLastError());
+  // the adjoint state has homogeneous boundary data; the prescribed values
+  // enter only the forward state's local fields in the viscosity gradient
+  const bool bd = ctx->has_bd;
+  ctx->has_bd = false;
   hdgmg_status result = hdgmg_solve(ctx, ctx->adj_f, gf_qp, ctx->adj_p, ast, info);
+  ctx->has_bd = bd;
   if (result < 0) return result;
   // dJ/df = w_q |K| u_adj(x_q)
   launch_data_weight(ctx->st, ctx->Q, KL.X, KL.cells, KL.nc, gf_qp, 0, gf_qp);

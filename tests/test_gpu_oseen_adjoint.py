@@ -144,3 +144,55 @@ def test_oseen_adjoint_matches_dense_adjoint(name):
         assert (a <= b + 2) if mixed else abs(a - b) <= 1, (its_g, its_o)
     sf.close()
     sa.close()
+
+
+@pytest.mark.parametrize("with_wind", [False, True])
+def test_adjoint_with_lid_data(with_wind):
+    # tangential Dirichlet data on the top side: the forward solve carries
+    # the lid, the adjoint has homogeneous data, dJ/dnu keeps the lid in the
+    # forward state's lifting
+    import paper_2303_06762_amd as hd
+    name = "k2"
+    n, nr, k, beta, scale, kw = CASES[name]
+    o = oracle_case(name)
+    lv = o["levels"][-1]
+    lid = oseen.lid_dirichlet(lv, k)
+    bd = dev(np.array([lid[E] for E in np.where(lv.int_id < 0)[0]]))
+    winds = None
+    if with_wind:
+        pr0 = hdg.Problem(lv, k, 1.0, 1.0, 1e2)
+        f0 = synth.source_uniform(100, 1, lv.n_cells, (k + 2) ** 2)[0]
+        lam0, p00 = pr0.solve_direct(f0)
+        winds = [(lambda X, w=w: scale * w(X)) for w in oseen.state_wind(pr0, lam0, p00, f0)]
+    fwd = oseen.OseenProblem(lv, k, o["nu"], beta, 1e2, winds, lid)
+    adj = oseen.OseenProblem(lv, k, o["nu"], beta, 1e2, winds, transpose=True)
+    J0, gf0, gnu0, _ = adjoint.gradients(fwd, o["f"], o["ut"], prob_adj=adj)
+    _note(f"lid adjoint wind={with_wind}")
+
+    def make(transpose):
+        s = hd.Solver(o["c"], o["t"], nr, k, beta, o["nu"], 1e2, oseen=1 if with_wind else 0,
+                      transpose=transpose, **kw)
+        if with_wind:
+            s.set_wind(dev(o["wq"]))
+        s.set_dirichlet(bd)
+        s.assemble()
+        return s
+
+    sf = make(0)
+    u, p, state, info, st = sf.solve(dev(o["f"]))
+    assert st == 0, info
+    uh = host(u)
+    assert abs(adjoint.misfit(fwd, uh, o["ut"]) - J0) <= 1e-8 * abs(J0)
+    gu = adjoint.misfit_grad(fwd, uh, o["ut"])
+    sa = make(1) if with_wind else sf
+    gf, gnu, ast, ainfo, st = sa.solve_adjoint(dev(o["f"]), state, dev(gu))
+    assert st == 0, ainfo
+    gf1, gnu1 = host(gf), host(gnu)
+    assert np.abs(gf1 - gf0).max() <= 1e-6 * np.abs(gf0).max(), np.abs(gf1 - gf0).max()
+    assert np.abs(gnu1 - gnu0).max() <= 1e-6 * np.abs(gnu0).max(), np.abs(gnu1 - gnu0).max()
+    # the forward context still solves with its lid afterwards
+    u2, _, _, _, st = sf.solve(dev(o["f"]))
+    assert st == 0 and np.abs(host(u2) - uh).max() <= 1e-12 * np.abs(uh).max()
+    sf.close()
+    if with_wind:
+        sa.close()

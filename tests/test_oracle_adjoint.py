@@ -235,3 +235,43 @@ def test_oseen_method_adjoint_reaches_dense_adjoint():
     assert np.abs(gf1 - gf0).max() <= 1e-7 * np.abs(gf0).max()
     assert np.abs(gnu1 - gnu0).max() <= 1e-7 * np.abs(gnu0).max()
     assert max(sa.its) <= 60, sa.its
+
+
+@pytest.mark.parametrize("with_wind", [False, True])
+def test_lid_data_gradients_match_central_differences(with_wind):
+    # Tangential Dirichlet data on the top side (the cavity's lid): the
+    # adjoint keeps homogeneous data, the forward lifting keeps the lid.
+    k = 1
+    levels, lv, nu, beta, winds, f, ut = oseen_case(k)
+    winds = winds if with_wind else None
+    lid = oseen.lid_dirichlet(lv, k)
+    fwd = oseen.OseenProblem(lv, k, nu, beta, 1e2, winds, lid)
+    adj = oseen.OseenProblem(lv, k, nu, beta, 1e2, winds, transpose=True)
+    J, gf, gnu, (lam_a, _) = adjoint.gradients(fwd, f, ut, prob_adj=adj)
+
+    def Jof(nu_, f_):
+        pr = oseen.OseenProblem(lv, k, nu_, beta, 1e2, winds, lid)
+        lam, p0 = pr.solve_direct(f_)
+        return adjoint.misfit(pr, adjoint.velocity(pr, lam, p0, f_), ut)
+
+    h = 1e-4
+    for K in (0, 9, lv.n_cells - 1):
+        e = np.zeros(lv.n_cells)
+        e[K] = h * nu[K]
+        fd = (Jof(nu + e, f) - Jof(nu - e, f)) / (2 * e[K])
+        assert abs(fd - gnu[K]) <= 1e-6 * np.abs(gnu).max(), (K, fd, gnu[K])
+    rng = np.random.default_rng(2)
+    for _ in range(4):
+        K, q, i = rng.integers(lv.n_cells), rng.integers(f.shape[1]), rng.integers(2)
+        fp, fm = f.copy(), f.copy()
+        fp[K, q, i] += h
+        fm[K, q, i] -= h
+        fd = (Jof(nu, fp) - Jof(nu, fm)) / (2 * h)
+        assert abs(fd - gf[K, q, i]) <= 1e-8 * np.abs(gf).max() + 1e-12
+    # dropping the lid from the forward lifting in dJ/dnu is detectable
+    lam, p0 = fwd.solve_direct(f)
+    f_a = adjoint.misfit_grad(fwd, adjoint.velocity(fwd, lam, p0, f), ut) / adjoint.weights(fwd)[:, :, None]
+    gnu_nolid = np.array([adjoint.grad_nu_cell(e, hdg.Problem.local(fwd, lam, K), f[K], adj.local(lam_a, K),
+                                               f_a[K], adj.elems[K])
+                          for K, e in enumerate(fwd.elems)])
+    assert np.abs(gnu_nolid - gnu).max() >= 1e-2 * np.abs(gnu).max()
