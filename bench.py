@@ -75,7 +75,10 @@ def oseen_workload(hd, synth, torch, np, steps, re, k=3, n_refine=5):
     body force sum_{a,b=1..3} c_ab sin(a pi x) sin(b pi y) (c ~ U[-1,1),
     seed 2); a Stokes solve then `steps` Picard steps, each AL-Uzawa with
     FGMRES(50) preconditioned by the FP32-storage V-cycle.  Timed: the
-    solves (each step's re-assembly reported separately)."""
+    solves (each step's re-assembly reported separately).  Then the adjoint
+    of the last Picard step's Oseen system (its wind fixed) for the kinetic
+    energy J = sum_{K,q} w_q |K| |u(x_q)|^2: a context holding A^T (assembled,
+    timed apart) and one adjoint solve giving dJ/df and dJ/dnu."""
     c, t = synth.kuhn_square(4)
     nu = 1.0 / re
     s = hd.Solver(c, t, n_refine, k, 0.0, nu, 1e2 * nu, oseen=1, vcycle_precision=1)
@@ -89,10 +92,11 @@ def oseen_workload(hd, synth, torch, np, steps, re, k=3, n_refine=5):
     f = torch.as_tensor(f, device="cuda")
     s.set_dirichlet(s.lid_data())
     t_solve = t_asm = 0.0
-    its, dus, x0, u_prev = [], [], None, None
+    its, dus, x0, u_prev, w_last = [], [], None, None, None
     for n in range(steps + 1):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        w_last = u_prev
         s.set_wind(None if u_prev is None else u_prev)
         s.assemble()
         torch.cuda.synchronize()
@@ -105,11 +109,31 @@ def oseen_workload(hd, synth, torch, np, steps, re, k=3, n_refine=5):
         if u_prev is not None:
             dus.append(float((u - u_prev).abs().max()))
         u_prev, x0 = u, state[:s.n_skel]
+    adj = None
+    if w_last is not None:
+        sa = hd.Solver(c, t, n_refine, k, 0.0, nu, 1e2 * nu, oseen=1, vcycle_precision=1, transpose=1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sa.set_wind(w_last)
+        sa.set_dirichlet(s.lid_data())
+        sa.assemble()
+        torch.cuda.synchronize()
+        t_aasm = time.perf_counter() - t0
+        gu = 2.0 * s.data_weights()[..., None] * u_prev
+        t0 = time.perf_counter()
+        gf, gnu, _, ainfo, ast = sa.solve_adjoint(f, state, gu)
+        torch.cuda.synchronize()
+        t_adj = time.perf_counter() - t0
+        adj = {"value": s.n_skel / t_adj, "unit": "skeleton DOFs/s", "status": ast, "solve_s": t_adj,
+               "assemble_s": t_aasm, "fgmres_its_per_uzawa_step": ainfo["its"],
+               "grad_norms": {"f": float(gf.norm()), "nu": float(gnu.norm())},
+               "functional": "kinetic energy sum w_q |K| |u(x_q)|^2 at the last Picard step, wind fixed"}
+        sa.close()
     out = {"workload": f"lid-driven cavity, 128x128 structured triangulation ({s.n_cells} cells, {s.levels} "
                        f"levels), k={k}, Re={re:g}, beta=0, eps^-1=1e2 nu; Stokes solve + {steps} Picard steps",
            "n_skel": s.n_skel, "value": s.n_skel * (steps + 1) / t_solve, "unit": "skeleton DOFs/s",
            "solve_s": t_solve, "assemble_s_total": t_asm, "fgmres_its_per_uzawa_step": its,
-           "picard_max_du": dus,
+           "picard_max_du": dus, "adjoint_last_step": adj,
            "precision": "V-cycle operators FP32, FGMRES(50) and everything else FP64"}
     s.close()
     return out

@@ -134,7 +134,22 @@ typedef struct {
   int its[HDGMG_MAX_UZAWA];        /* inner iterations per Uzawa step       */
   double rel_res[HDGMG_MAX_UZAWA]; /* final ||r||/||r0|| per Uzawa step     */
   double dp_l2[HDGMG_MAX_UZAWA];   /* ||p_n - p_{n-1}||_L2 per step         */
+  double div_l2;                   /* ||div u_h||_L2 of the returned velocity:
+                                      div u_h is constant per cell (its
+                                      normal traces), equal to
+                                      (p_n - p_{n-1}) / (-eps^-1) of the
+                                      last step                             */
+  double t_solve;                  /* host wall time of the call, seconds   */
 } hdgmg_info;
+
+/* Device allocator of the caller (e.g. PyTorch's caching allocator):
+ * alloc returns `bytes` bytes of device memory aligned to at least 256 bytes,
+ * or NULL on failure; free releases a pointer alloc returned.  Both are
+ * called on the thread that called the library, only from hdgmg_setup,
+ * hdgmg_assemble, hdgmg_solve_adjoint (its first call) and hdgmg_destroy,
+ * after the context's stream has been synchronised for frees. */
+typedef void* (*hdgmg_alloc_fn)(size_t bytes, void* alloc_ctx);
+typedef void (*hdgmg_free_fn)(void* ptr, void* alloc_ctx);
 
 /* Build the mesh hierarchy, skeleton topology, vertex patches with their
  * colouring, and the intergrid transfers; allocate device workspace.
@@ -144,13 +159,20 @@ typedef struct {
  *          finest cells (per-cell viscosity); all > 0
  *   gamma  > 0, eps^-1
  *   opts   host, may be NULL for the defaults
- *   stream hipStream_t used for every device operation (NULL: default)
+ *   stream hipStream_t used for every device operation (NULL: a stream of
+ *          the library's own)
+ *   alloc_fn, free_fn, alloc_ctx  the caller's device allocator, through which
+ *          every device buffer of the context is allocated and released
+ *          (workspace, operators, factors, transfers); both NULL: hipMalloc
+ *          and hipFree.  Giving only one is EINVAL.
  * On success *out receives a new context (release with hdgmg_destroy).
  * Errors: EINVAL (bad k, beta, nu, gamma, opts), EMESH (dim != 2, bad
  * indices, zero-area cell, facet shared by > 2 cells), ENOMEM, EHIP. */
 hdgmg_status hdgmg_setup(const hdgmg_mesh* mesh, int k, double beta,
                          const double* nu, int nu_len, double gamma,
-                         const hdgmg_opts* opts, void* stream, hdgmg_ctx** out);
+                         const hdgmg_opts* opts, void* stream,
+                         hdgmg_alloc_fn alloc_fn, hdgmg_free_fn free_fn,
+                         void* alloc_ctx, hdgmg_ctx** out);
 
 /* Element local solvers and static condensation of the order-k scheme
  * (stWeak -> stOptForm, with the AL term of stALform), the lowest-order

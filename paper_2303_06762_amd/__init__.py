@@ -7,6 +7,7 @@ and raises otherwise -- there is no fallback.
 """
 import ctypes
 import os
+import sys
 
 import numpy as np
 
@@ -36,7 +37,39 @@ class Opts(ctypes.Structure):
 
 class Info(ctypes.Structure):
     _fields_ = [("uzawa_steps", ctypes.c_int), ("its", ctypes.c_int * MAX_UZAWA),
-                ("rel_res", ctypes.c_double * MAX_UZAWA), ("dp_l2", ctypes.c_double * MAX_UZAWA)]
+                ("rel_res", ctypes.c_double * MAX_UZAWA), ("dp_l2", ctypes.c_double * MAX_UZAWA),
+                ("div_l2", ctypes.c_double), ("t_solve", ctypes.c_double)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class TorchAllocator:
+    """Device memory of a context from PyTorch's caching allocator: each
+    buffer the library asks for is a uint8 CUDA tensor kept alive here
+    until the library frees it (hdgmg_alloc_fn / hdgmg_free_fn)."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.live = {}
+        self.alloc = ALLOC_FN(self._alloc)
+        self.free = FREE_FN(self._free)
+
+    def _alloc(self, nbytes, _ctx):
+        try:
+            t = self.torch.empty(int(nbytes), dtype=self.torch.uint8, device="cuda")
+        except Exception:
+            return None
+        p = t.data_ptr()
+        self.live[p] = t
+        return p
+
+    def _free(self, ptr, _ctx):
+        self.live.pop(ptr, None)
+
+    def bytes(self):
+        return sum(t.numel() for t in self.live.values())
 
 
 class HdgmgError(RuntimeError):
@@ -64,7 +97,7 @@ def lib():
     L.hdgmg_default_opts.argtypes = [ctypes.POINTER(Opts)]
     L.hdgmg_default_opts.restype = None
     L.hdgmg_setup.argtypes = [ctypes.POINTER(Mesh), i32, dbl, ctypes.POINTER(dbl), i32, dbl,
-                              ctypes.POINTER(Opts), vp, ctypes.POINTER(vp)]
+                              ctypes.POINTER(Opts), vp, ALLOC_FN, FREE_FN, vp, ctypes.POINTER(vp)]
     L.hdgmg_setup.restype = i32
     L.hdgmg_assemble.argtypes = [vp]
     L.hdgmg_assemble.restype = i32
@@ -117,7 +150,8 @@ class Solver:
     """hdgmg context: setup(mesh hierarchy, k, beta, nu, gamma) -> assemble ->
     solve(f) -> (u, p).  Tensors are torch float64 CUDA tensors."""
 
-    def __init__(self, coords, cells, n_refine, k, beta, nu, gamma, opts=None, stream=None, **kw):
+    def __init__(self, coords, cells, n_refine, k, beta, nu, gamma, opts=None, stream=None, allocator="torch",
+                 **kw):
         import torch
         self.torch = torch
         L = lib()
@@ -133,11 +167,21 @@ class Solver:
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
+        # device memory: PyTorch's caching allocator ("torch") or the
+        # library's own hipMalloc ("hip")
+        if allocator == "torch":
+            self.allocator = TorchAllocator(torch)
+            afn, ffn = self.allocator.alloc, self.allocator.free
+        elif allocator == "hip":
+            self.allocator = None
+            afn, ffn = ALLOC_FN(), FREE_FN()
+        else:
+            raise ValueError("allocator must be 'torch' or 'hip'")
         h = ctypes.c_void_p()
         st = L.hdgmg_setup(ctypes.byref(m), int(k), float(beta),
                            nu.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(nu),
                            float(gamma), ctypes.byref(opts), ctypes.c_void_p(stream.cuda_stream),
-                           ctypes.byref(h))
+                           afn, ffn, None, ctypes.byref(h))
         if st != 0:
             raise HdgmgError(st, L.hdgmg_last_error(None).decode())
         self._h = h
@@ -155,6 +199,10 @@ class Solver:
         self._h = None
 
     def __del__(self):
+        # at interpreter exit the process releases the device memory; the
+        # allocator callbacks must not run into a half torn-down torch
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -216,7 +264,7 @@ class Solver:
                                               ctypes.byref(info)), allow=(0, 1))
         n = info.uzawa_steps
         d = dict(uzawa_steps=n, its=list(info.its[:n]), rel_res=list(info.rel_res[:n]),
-                 dp_l2=list(info.dp_l2[:n]))
+                 dp_l2=list(info.dp_l2[:n]), div_l2=info.div_l2, t_solve=info.t_solve)
         return u, p, state, d, st
 
     def solve_adjoint(self, f_qp, state, gu_qp, gnu=None, adj_state=None):
@@ -235,7 +283,7 @@ class Solver:
                          allow=(0, 1))
         n = info.uzawa_steps
         d = dict(uzawa_steps=n, its=list(info.its[:n]), rel_res=list(info.rel_res[:n]),
-                 dp_l2=list(info.dp_l2[:n]))
+                 dp_l2=list(info.dp_l2[:n]), div_l2=info.div_l2, t_solve=info.t_solve)
         return gf, gnu, adj_state, d, st
 
     def set_wind(self, w_qp):

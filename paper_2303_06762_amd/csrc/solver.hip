@@ -207,6 +207,10 @@ struct hdgmg_ctx {
   bool assembled = false;
   size_t bytes = 0;
   std::vector<void*> allocs;
+  // caller's device allocator (null: hipMalloc / hipFree)
+  hdgmg_alloc_fn alloc_fn = nullptr;
+  hdgmg_free_fn free_fn = nullptr;
+  void* alloc_ctx = nullptr;
   // live kernel timers (hdgmg_kernel_timer)
   struct KTimer {
     bool on = false;
@@ -238,13 +242,27 @@ namespace {
     }                                                                                \
   } while (0)
 
+// Device memory through the caller's allocator when one was given at setup
+// (e.g. PyTorch's caching allocator), else hipMalloc / hipFree.
+void* dmalloc(hdgmg_ctx* ctx, size_t bytes) {
+  if (ctx->alloc_fn) return ctx->alloc_fn(bytes, ctx->alloc_ctx);
+  void* v = nullptr;
+  return hipMalloc(&v, bytes) == hipSuccess ? v : nullptr;
+}
+void dfree(hdgmg_ctx* ctx, void* p) {
+  if (!p) return;
+  if (ctx->free_fn)
+    ctx->free_fn(p, ctx->alloc_ctx);
+  else
+    (void)hipFree(p);
+}
+
 template <class T>
 hdgmg_status dalloc(hdgmg_ctx* ctx, T** p, size_t n) {
   *p = nullptr;
   if (n == 0) return HDGMG_OK;
-  void* v = nullptr;
-  hipError_t e = hipMalloc(&v, n * sizeof(T));
-  if (e != hipSuccess) {
+  void* v = dmalloc(ctx, n * sizeof(T));
+  if (!v) {
     ctx->err = "device allocation of " + std::to_string(n * sizeof(T)) + " bytes failed";
     return HDGMG_ENOMEM;
   }
@@ -1373,17 +1391,23 @@ void hdgmg_destroy(hdgmg_ctx* ctx) {
   if (ctx->st) (void)hipStreamSynchronize(ctx->st);
   drop_graph(ctx);
   for (auto& T : ctx->timers) kt_clear(T);
-  for (void* p : ctx->allocs) (void)hipFree(p);
+  for (auto& a : ctx->asm_allocs) dfree(ctx, a.first);
+  for (void* p : ctx->allocs) dfree(ctx, p);
   if (ctx->own) (void)hipStreamDestroy(ctx->own);
   delete ctx;
 }
 
 hdgmg_status hdgmg_setup(const hdgmg_mesh* mesh, int k, double beta, const double* nu, int nu_len,
-                         double gamma, const hdgmg_opts* opts, void* stream, hdgmg_ctx** out) {
+                         double gamma, const hdgmg_opts* opts, void* stream, hdgmg_alloc_fn alloc_fn,
+                         hdgmg_free_fn free_fn, void* alloc_ctx, hdgmg_ctx** out) {
   if (out) *out = nullptr;
   g_setup_error.clear();
   if (!mesh || !out || !nu) {
     g_setup_error = "null argument";
+    return HDGMG_EINVAL;
+  }
+  if ((alloc_fn == nullptr) != (free_fn == nullptr)) {
+    g_setup_error = "give both allocator callbacks or neither";
     return HDGMG_EINVAL;
   }
   if (mesh->dim != 2 || mesh->n_vertices < 3 || mesh->n_cells < 1 || !mesh->coords || !mesh->cells ||
@@ -1406,6 +1430,9 @@ hdgmg_status hdgmg_setup(const hdgmg_mesh* mesh, int k, double beta, const doubl
       return HDGMG_EINVAL;
     }
   hdgmg_ctx* ctx = new hdgmg_ctx();
+  ctx->alloc_fn = alloc_fn;
+  ctx->free_fn = free_fn;
+  ctx->alloc_ctx = alloc_ctx;
   ctx->k = k;
   ctx->beta = beta;
   ctx->gamma = gamma;
@@ -1581,7 +1608,7 @@ hdgmg_status hdgmg_assemble(hdgmg_ctx* ctx) {
   drop_graph(ctx);
   HIPC(hipStreamSynchronize(ctx->st));
   for (auto& a : ctx->asm_allocs) {
-    (void)hipFree(a.first);
+    dfree(ctx, a.first);
     ctx->bytes -= a.second;
   }
   ctx->asm_allocs.clear();
@@ -1779,6 +1806,7 @@ hdgmg_status hdgmg_solve_x0(hdgmg_ctx* ctx, const double* f_qp, const double* x0
     return HDGMG_ESTATE;
   }
   if (info) std::memset(info, 0, sizeof(*info));
+  const auto t_start = std::chrono::steady_clock::now();
   hipStream_t st = ctx->st;
   const DevLevel& KL = ctx->K;
   if (x0)
@@ -1809,6 +1837,7 @@ hdgmg_status hdgmg_solve_x0(hdgmg_ctx* ctx, const double* f_qp, const double* x0
       info->its[n] = its;
       info->rel_res[n] = rel;
       info->dp_l2[n] = dn;
+      info->div_l2 = dn / ctx->gamma;
     }
     if (dn <= ctx->opts.uzawa_tol * std::max(1.0, pn)) break;
     if (n == ctx->opts.uzawa_max - 1) {
@@ -1828,6 +1857,7 @@ hdgmg_status hdgmg_solve_x0(hdgmg_ctx* ctx, const double* f_qp, const double* x0
   }
   TRY(hdgmg_recover(ctx, f_qp, stt, u_qp, p_qp));
   HIPC(hipStreamSynchronize(st));
+  if (info) info->t_solve = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   return result;
 }
 
