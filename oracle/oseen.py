@@ -27,6 +27,15 @@ imports it).
   residual; x_0 = the latest skeleton iterate.
 * Tangential Dirichlet data on boundary facets (the lid of the cavity):
   uhat . t_F prescribed per boundary facet and mode; moved to the load.
+* Newton linearisation (Sec. 4.2): the Jacobian adds to the Picard form the
+  term C_h(du; u_prev, v) -- the previous velocity transported by the
+  increment's flux -- with the upwind switch frozen on u_prev.n_K (taken
+  point by point; where it vanishes the facet term is dropped, as in the
+  Picard form).  Solving for u_n = u_prev + du directly, the right-hand side
+  is f plus the functional C_h(u_prev; u_prev, v), which by bilinearity (for
+  the frozen switch) equals the Picard matrix applied to the previous local
+  state.  The lowest-order levels of MG_h keep the Picard operators of the
+  RT0-projected wind.
 * Transposed (adjoint) systems, transpose=True: every cell's convection
   matrix enters transposed (the Stokes part is symmetric), on the order-k
   level and on every lowest-order level.  Static condensation commutes with
@@ -95,12 +104,63 @@ def convection_matrix(e, wind):
     return C
 
 
+def newton_matrix(e, wind, z_prev):
+    """N [nz, nz] (row: test, column: trial) of the Newton term
+    C_h(du; u_prev, v) for the increment du (trial: RT coefficients only),
+    the previous velocity wind(X) (u_prev in this cell) and its local state
+    z_prev (RT coefficients, then tangential facet traces; the upwind value
+    on a facet is the cell's trace t(u_prev) where u_prev.n_K > 0 and the
+    facet unknown uhat_prev where u_prev.n_K < 0)."""
+    lv, K, k, m = e.lv, e.K, e.k, e.m
+    na, nz = e.na, e.nz
+    N = np.zeros((nz, nz))
+    nc = convection_points(k)
+    vs = np.sort(lv.cells[K])
+    X, w = quad.data_points(lv.coords[vs], nc)
+    wq = w * e.area
+    val, grd, _ = e.rt.eval(X)
+    U = wind(X)
+    # - sum_ij (u_prev,i du_j, d_j v_i): trial a (du = u_a), test b
+    N[:na, :na] -= np.einsum("q,qi,qaj,qbij->ba", wq, U, val, grd)
+    s, om = quad.gauss_legendre01(nc)
+    phi = hdg.facet_basis(k, s)
+    for f in range(3):
+        E = lv.cell_facets[K, f]
+        X0 = lv.coords[lv.edges[E, 0]]
+        X1 = lv.coords[lv.edges[E, 1]]
+        L = lv.length[E]
+        t = lv.tangent[E]
+        nK = lv.sigma[K, f] * lv.normal[E]
+        xl = X0[None, :] + s[:, None] * (X1 - X0)[None, :]
+        Pv, _, _ = e.rt.eval(xl)
+        ut = Pv @ t                                  # [l, a]
+        un = Pv @ nK                                 # [l, a]: du.n_K per trial
+        wn = wind(xl) @ nK
+        for l in range(len(s)):
+            if wn[l] == 0.0:
+                continue
+            if wn[l] > 0:
+                up = ut[l] @ z_prev[:na]
+            else:
+                up = phi[l] @ z_prev[na + f * m:na + (f + 1) * m]
+            test = np.zeros(nz)
+            test[:na] = ut[l]
+            test[na + f * m:na + (f + 1) * m] = -phi[l]
+            trial = np.zeros(nz)
+            trial[:na] = un[l]
+            N += (L * om[l] * up) * np.outer(test, trial)
+    return N
+
+
 class OseenElement:
     """A cell of the Picard-linearised scheme: the Stokes element's forms
-    plus the convection matrix, condensed without assuming symmetry."""
+    plus the convection matrix, condensed without assuming symmetry.
+    Fz_extra: an additional local load (both interior and facet rows), the
+    Newton right-hand side."""
 
-    def __init__(self, base, C):
+    def __init__(self, base, C, Fz_extra=None):
         self.base = base
+        self.Fz_extra = Fz_extra
         self.H = base.H + C
         E, Zh, H = base.E, base.Zh, self.H
         HE = H @ E
@@ -115,15 +175,19 @@ class OseenElement:
                      "M", "R", "P", "rt", "mean_psi", "nu"):
             setattr(self, name, getattr(base, name))
 
-    def load(self, f_q):
+    def load_z(self, f_q):
         Fz = self.base.load_z(f_q)
+        return Fz if self.Fz_extra is None else Fz + self.Fz_extra
+
+    def load(self, f_q):
+        Fz = self.load_z(f_q)
         g = self.E.T @ Fz
         if self.Kyy is not None:
             g = g - self.EHZ @ np.linalg.solve(self.Kyy, self.Zh.T @ Fz)
         return g
 
     def recover_z(self, lam, f_q):
-        Fz = self.base.load_z(f_q)
+        Fz = self.load_z(f_q)
         z = self.E @ lam
         if self.Kyy is not None:
             z = z + self.Zh @ np.linalg.solve(self.Kyy, self.Zh.T @ (Fz - self.H @ z))
@@ -158,13 +222,17 @@ class OseenProblem(hdg.Problem):
     coefficients on boundary facets (None: homogeneous).  transpose: the
     transposed system (convection matrices transposed per cell)."""
 
-    def __init__(self, lv, k, nu, beta, gamma, winds=None, dirichlet=None, transpose=False):
+    def __init__(self, lv, k, nu, beta, gamma, winds=None, dirichlet=None, transpose=False, newton_z=None):
         super().__init__(lv, k, nu, beta, gamma)
         if winds is not None:
-            def conv(e, K):
+            def cell(e, K):
                 C = convection_matrix(e, winds[K])
-                return C.T.copy() if transpose else C
-            self.elems = [OseenElement(e, conv(e, K)) for K, e in enumerate(self.elems)]
+                if newton_z is not None:
+                    # Jacobian C + N, load C z_prev (= C_h(u_prev; u_prev, .))
+                    Nm = newton_matrix(e, winds[K], newton_z[K])
+                    return OseenElement(e, C + Nm, C @ newton_z[K])
+                return OseenElement(e, C.T.copy() if transpose else C)
+            self.elems = [cell(e, K) for K, e in enumerate(self.elems)]
         self.dirichlet = dirichlet
 
     def boundary_local(self, K):
@@ -353,11 +421,11 @@ class OseenSetup:
     Oseen hierarchy."""
 
     def __init__(self, levels, k, nu, beta, gamma, winds=None, dirichlet=None, m_p=1, m_h=1,
-                 q=1, growth=2, restart=50, transpose=False):
+                 q=1, growth=2, restart=50, transpose=False, newton_z=None):
         self.levels = levels
         self.lv = levels[-1]
         self.k = k
-        self.prob = OseenProblem(self.lv, k, nu, beta, gamma, winds, dirichlet, transpose)
+        self.prob = OseenProblem(self.lv, k, nu, beta, gamma, winds, dirichlet, transpose, newton_z)
         self.Aeps = self.prob.matrix_Aeps().tocsr()
         self.D = self.prob.matrix_D().tocsr()
         self.eps_inv = self.prob.eps_inv
@@ -418,4 +486,59 @@ def picard(levels, k, nu, beta, gamma, f_qp, n_steps, dirichlet=None, direct=Fal
         out.append(r)
         winds = state_wind(S.prob, r["lam"], r["p0"], f_qp)
         lam = r["lam"]
+    return out
+
+
+def local_states(prob, lam, f_qp):
+    """Per-cell local state z (RT coefficients, tangential facet traces) of
+    a solved skeleton vector (boundary values included)."""
+    return [e.recover_z(prob.local(lam, K), f_qp[K])[0] for K, e in enumerate(prob.elems)]
+
+
+def l2_diff(prob, u1, u2):
+    W = np.array([e.wq for e in prob.elems])
+    return float(np.sqrt(np.sum(W[:, :, None] * (u1 - u2) ** 2)))
+
+
+def picard_newton(levels, k, nu, beta, gamma, f_qp, dirichlet=None, eps_picard=1e-4, newton_rtol=1e-8,
+                  newton_atol=1e-10, max_picard=50, max_newton=20, direct=False, **kw):
+    """Alg. 3: a Stokes solve, Picard steps until ||u_n - u_{n-1}||_0 <
+    eps_picard, then Newton steps until ||u_n - u_{n-1}||_0 <=
+    max(newton_rtol ||u_n||_0, newton_atol); every step starts from the
+    previous skeleton vector.  Returns the per-step dicts (kind, lam, p0, u,
+    its, du)."""
+    out = []
+    winds = zs = lam = u_prev = None
+    kind = "stokes"
+    n_p = n_n = 0
+    while True:
+        nz_ = zs if kind == "newton" else None
+        if direct:
+            prob = OseenProblem(levels[-1], k, nu, beta, gamma, winds, dirichlet, newton_z=nz_)
+            lam_d, p_d = prob.solve_direct(f_qp)
+            r = dict(lam=lam_d, p0=p_d, its=[])
+            S = None
+        else:
+            S = OseenSetup(levels, k, nu, beta, gamma, winds, dirichlet, newton_z=nz_, **kw)
+            prob = S.prob
+            r = S.solve(f_qp, lam0=lam)
+        u, _, _, _ = prob.recover(r["lam"], r["p0"], f_qp)
+        du = None if u_prev is None else l2_diff(prob, u, u_prev)
+        r.update(kind=kind, u=u, du=du, setup=S, prob=prob)
+        out.append(r)
+        unorm = l2_diff(prob, u, 0.0 * u)
+        if kind == "newton":
+            n_n += 1
+            if du <= max(newton_rtol * unorm, newton_atol) or n_n >= max_newton:
+                break
+        else:
+            if kind == "picard":
+                n_p += 1
+            if kind == "picard" and (du < eps_picard or n_p >= max_picard):
+                kind = "newton"
+            elif kind == "stokes":
+                kind = "picard"
+        winds = state_wind(prob, r["lam"], r["p0"], f_qp)
+        zs = local_states(prob, r["lam"], f_qp)
+        lam, u_prev = r["lam"], u
     return out
