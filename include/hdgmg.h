@@ -257,6 +257,21 @@ hdgmg_status hdgmg_solve_x0(hdgmg_ctx* ctx, const double* f_qp, const double* x0
  * for a degenerate fit. */
 hdgmg_status hdgmg_set_wind(hdgmg_ctx* ctx, const double* w_qp);
 
+/* Newton linearisation (Sec. 4.2): the next hdgmg_assemble builds the
+ * Jacobian of the scheme (nsWeak) at the previous state u_prev, i.e. the
+ * Picard form plus C_h(du; u_prev, v) with the upwind switch frozen on
+ * u_prev . n_K, and every load gains C_h(u_prev; u_prev, v), so that
+ * hdgmg_solve returns the Newton iterate u_n = u_prev + du itself.
+ *   state_prev  device [N_skel (+ n_cells, ignored)]: the skeleton vector of
+ *          u_prev (as written by hdgmg_solve); copied during the call.  Its
+ *          velocity at the data points must be the wind last given to
+ *          hdgmg_set_wind; on boundary facets the tangential values are the
+ *          Dirichlet data of hdgmg_set_dirichlet.  NULL: back to Picard.
+ * The lowest-order levels of MG_h keep the Picard operators of the
+ * RT0-projected wind.  hdgmg_set_wind clears the Newton state.  Requires
+ * opts.oseen = 1, opts.transpose = 0, k >= 1 and a wind (else ESTATE). */
+hdgmg_status hdgmg_set_newton(hdgmg_ctx* ctx, const double* state_prev);
+
 /* Tangential Dirichlet data on the boundary facets (the lid of a cavity):
  * uhat_b device [n_boundary_facets][k+1], per boundary facet (in facet
  * order, see hdgmg_export what 3) the coefficients of uhat . t_F in the

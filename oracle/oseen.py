@@ -126,6 +126,10 @@ def newton_matrix(e, wind, z_prev):
     phi = hdg.facet_basis(k, s)
     for f in range(3):
         E = lv.cell_facets[K, f]
+        if lv.int_id[E] < 0:
+            # boundary facet: the increment's normal trace vanishes there
+            # (and u_prev.n_K is zero up to rounding, so no switch is taken)
+            continue
         X0 = lv.coords[lv.edges[E, 0]]
         X1 = lv.coords[lv.edges[E, 1]]
         L = lv.length[E]

@@ -79,7 +79,8 @@ class HdgmgError(RuntimeError):
 
 
 SYMBOLS = ["hdgmg_default_opts", "hdgmg_setup", "hdgmg_assemble", "hdgmg_solve",
-           "hdgmg_solve_adjoint", "hdgmg_solve_x0", "hdgmg_set_wind", "hdgmg_set_dirichlet", "hdgmg_rhs",
+           "hdgmg_solve_adjoint", "hdgmg_solve_x0", "hdgmg_set_wind", "hdgmg_set_newton", "hdgmg_set_dirichlet",
+           "hdgmg_rhs",
            "hdgmg_apply", "hdgmg_precondition", "hdgmg_inner_solve", "hdgmg_recover",
            "hdgmg_query", "hdgmg_export", "hdgmg_kernel_timer", "hdgmg_kernel_timer_read",
            "hdgmg_last_error", "hdgmg_destroy"]
@@ -107,7 +108,7 @@ def lib():
     L.hdgmg_solve_adjoint.restype = i32
     L.hdgmg_solve_x0.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(Info)]
     L.hdgmg_solve_x0.restype = i32
-    for name in ("hdgmg_set_wind", "hdgmg_set_dirichlet"):
+    for name in ("hdgmg_set_wind", "hdgmg_set_newton", "hdgmg_set_dirichlet"):
         getattr(L, name).argtypes = [vp, vp]
         getattr(L, name).restype = i32
     for name in ("hdgmg_rhs", "hdgmg_apply", "hdgmg_precondition"):
@@ -291,6 +292,13 @@ class Solver:
         convection); re-assemble afterwards."""
         self._check(lib().hdgmg_set_wind(self._h, ctypes.c_void_p(None) if w_qp is None else _ptr(w_qp)))
 
+    def set_newton(self, state_prev):
+        """Newton linearisation at the previous state (its skeleton vector,
+        whose velocity is the current wind); None: Picard.  Re-assemble
+        afterwards."""
+        self._check(lib().hdgmg_set_newton(self._h, ctypes.c_void_p(None) if state_prev is None
+                                           else _ptr(state_prev)))
+
     def set_dirichlet(self, uhat_b):
         """Tangential boundary coefficients [n_boundary_facets][k+1] (None:
         homogeneous)."""
@@ -412,5 +420,47 @@ def picard(solver, f_qp, steps, dirichlet=None):
             solver.assemble()
         u, p, state, info, st = solver.solve(f_qp, x0=x0)
         out.append((u, p, state, info, st))
+        x0 = state[:solver.n_skel]
+    return out
+
+
+def picard_newton(solver, f_qp, dirichlet=None, eps_picard=1e-4, newton_rtol=1e-8, newton_atol=1e-10,
+                  max_picard=50, max_newton=20):
+    """Alg. 3 on an opts.oseen Solver: a Stokes solve, Picard steps until
+    ||u_n - u_{n-1}||_0 < eps_picard, then Newton steps until
+    ||u_n - u_{n-1}||_0 <= max(newton_rtol ||u_n||_0, newton_atol); every
+    step starts from the previous skeleton vector.  Returns a list of dicts
+    (kind, u, p, state, info, status, du) per solve."""
+    torch = solver.torch
+    W = solver.data_weights()
+
+    def l2(d):
+        return float(torch.sqrt((W[..., None] * d * d).sum()))
+
+    if dirichlet is not None:
+        solver.set_dirichlet(dirichlet)
+    solver.set_wind(None)
+    solver.assemble()
+    out = []
+    kind, n_p, n_n = "stokes", 0, 0
+    x0 = None
+    while True:
+        u, p, state, info, st = solver.solve(f_qp, x0=x0)
+        du = None if not out else l2(u - out[-1]["u"])
+        out.append(dict(kind=kind, u=u, p=p, state=state, info=info, status=st, du=du))
+        if kind == "newton":
+            n_n += 1
+            if du <= max(newton_rtol * l2(u), newton_atol) or n_n >= max_newton:
+                break
+        elif kind == "picard":
+            n_p += 1
+            if du < eps_picard or n_p >= max_picard:
+                kind = "newton"
+        else:
+            kind = "picard"
+        solver.set_wind(u)
+        if kind == "newton":
+            solver.set_newton(state)
+        solver.assemble()
         x0 = state[:solver.n_skel]
     return out

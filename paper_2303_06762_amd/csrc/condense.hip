@@ -90,6 +90,9 @@ __global__ void __launch_bounds__(WL) k_condense_wave(ElemLevel E, double* __res
   __shared__ double M[nP * nP], H[nz * nz], Nm[nN * na], Dr[nP * na], mean[nP];
   __shared__ double A[D::nA];
   __shared__ double bu[6 * na], bm[nP], bphi[m], wv[2];
+  // Newton: the previous state's tangential traces per local facet and the
+  // Newton load C_h(u_prev; u_prev, .) on the test functions
+  __shared__ double tp[3 * m], nl[nz];
   __shared__ int piv[nkkt];
   __shared__ int sing;
   double* R = A;
@@ -108,6 +111,15 @@ __global__ void __launch_bounds__(WL) k_condense_wave(ElemLevel E, double* __res
   for (int e = lane; e < nP * na; e += WL) Dr[e] = 0.0;
   for (int e = lane; e < D::nR; e += WL) R[e] = 0.0;
   if (lane < nP) mean[lane] = 0.0;
+  const bool newton = conv && E.nw_lam != nullptr;
+  if (newton) {
+    for (int e = lane; e < nz; e += WL) nl[e] = 0.0;
+    for (int e = lane; e < 3 * m; e += WL) {
+      const int i = e / m, j = e % m;
+      const int d = E.cell_dofs[3 * c + i];
+      tp[e] = d >= 0 ? E.nw_lam[((long)d * 2 + 1) * m + j] : (E.bdl ? E.bdl[((long)c * 3 + i) * m + j] : 0.0);
+    }
+  }
   if (lane == 0) sing = 0;
   __syncthreads();
 
@@ -144,9 +156,19 @@ __global__ void __launch_bounds__(WL) k_condense_wave(ElemLevel E, double* __res
         const double g0 = wt * (wv[0] * ub[2] + wv[1] * ub[3]);
         const double g1 = wt * (wv[0] * ub[4] + wv[1] * ub[5]);
         h -= g0 * ua[0] + g1 * ua[1];
+        if (newton) {
+          // - sum_ij (u_prev,i du_j, d_j v_i) with du = u_a (u_prev = w)
+          h -= wt * (ua[0] * (wv[0] * ub[2] + wv[1] * ub[4]) + ua[1] * (wv[0] * ub[3] + wv[1] * ub[5]));
+        }
       }
       H[(long)b * nz + a] += h;
     }
+    if (newton)
+      for (int b = lane; b < na; b += WL) {
+        // Newton load, volume part: - (u_prev . (u_prev . grad) v_b)
+        const double* ub = bu + 6 * b;
+        nl[b] -= wt * (wv[0] * (wv[0] * ub[2] + wv[1] * ub[3]) + wv[1] * (wv[0] * ub[4] + wv[1] * ub[5]));
+      }
     __syncthreads();
   }
   if (lane < nP) mean[lane] /= g.area;
@@ -210,6 +232,32 @@ __global__ void __launch_bounds__(WL) k_condense_wave(ElemLevel E, double* __res
               H[(long)b * nz + tr] += tv * (bu[6 * tr] * t[0] + bu[6 * tr + 1] * t[1]);
             else
               H[(long)b * nz + na + i * m + tr] += tv * bphi[tr];
+          }
+          // (boundary facets: the increment's normal trace vanishes there and
+          // u_prev.n_K is zero up to rounding, so the term is left out)
+          if (newton && E.cell_dofs[3 * c + i] >= 0) {
+            __syncthreads();  // the Picard terms above touch the same entries
+            // upwind tangential value of the previous state: its own trace
+            // where w.n_K > 0, its facet unknown where w.n_K < 0
+            double up = 0.0;
+            if (wn > 0.0)
+              for (int cc = 0; cc < na; ++cc) up += wc[cc] * (bu[6 * cc] * t[0] + bu[6 * cc + 1] * t[1]);
+            else
+              for (int j = 0; j < m; ++j) up += tp[i * m + j] * bphi[j];
+            const double cu = CT->ws[l] * g.len[i] * up;
+            // <(du.n_K) up, t(v) - vhat>: trial du = u_a
+            for (int e = lane; e < ntest * na; e += WL) {
+              const int bt = e / na, tr = e % na;
+              const int b = bt < na ? bt : na + i * m + (bt - na);
+              const double tv = bt < na ? bu[6 * bt] * t[0] + bu[6 * bt + 1] * t[1] : -bphi[bt - na];
+              H[(long)b * nz + tr] += cu * tv * (bu[6 * tr] * nk[0] + bu[6 * tr + 1] * nk[1]);
+            }
+            // Newton load, facet part: (w.n_K) up (t(v) - vhat)
+            for (int bt = lane; bt < ntest; bt += WL) {
+              const int b = bt < na ? bt : na + i * m + (bt - na);
+              const double tv = bt < na ? bu[6 * bt] * t[0] + bu[6 * bt + 1] * t[1] : -bphi[bt - na];
+              nl[b] += cw * up * tv;
+            }
           }
         }
         __syncthreads();
@@ -345,6 +393,8 @@ __global__ void __launch_bounds__(WL) k_condense_wave(ElemLevel E, double* __res
     o += (long)na * 3 * m;
     for (int e = lane; e < nP; e += WL) F[(o + e) * nc] = mean[e];
   }
+  if (newton && E.nw_load)
+    for (int e = lane; e < nz; e += WL) E.nw_load[(long)e * E.nc + c] = nl[e];
   // ---- right-hand sides B = [[0, -H_at], [I, 0], [0, 0]] (columns c^n, c^t)
   for (int e = lane; e < nkkt * nK; e += WL) {
     const int r = e / nK, l = e % nK;

@@ -694,9 +694,11 @@ HDI long element_cached_ws_size(int k) {
 // EL_LOAD / EL_RECOVER from the factors kept by element_local(EL_CONDENSE):
 // the same local solve with the LU factors of the cell's KKT matrix, so only
 // the source term and two triangular solves are computed.  Inputs and
-// outputs as element_local.
+// outputs as element_local.  nx: an additional local load (Newton), nz
+// entries: RT test rows (added to the source moments) then tangential facet
+// rows (added to the condensed load's tangential rows).
 HDI void element_cached(const QuadTables& Q, const CellGeom& g, int mode, const double* f, const double* lam,
-                        double p0, WS fac, WS w, double* out) {
+                        double p0, WS fac, WS w, double* out, const WS* nx = nullptr) {
   const Dims D = dims_of(Q.k);
   const int nP = D.nP, na = D.na, m = D.m, nK = D.nK, nN = D.nN, nkkt = D.nkkt;
   const long oK = 0, oP = (long)nkkt * nkkt, oHta = oP + nkkt, oHat = oHta + 3L * m * na, oMean = oHat + 3L * m * na;
@@ -711,6 +713,8 @@ HDI void element_cached(const QuadTables& Q, const CellGeom& g, int mode, const 
     rt_basis(D, g, x1, x2, xp, u, gr, mono);
     for (int a = 0; a < na; ++a) F[a] += wt * (f[2 * q] * u[2 * a] + f[2 * q + 1] * u[2 * a + 1]);
   }
+  if (nx)
+    for (int a = 0; a < na; ++a) F[a] += (*nx)[a];
   for (int i = 0; i < nkkt; ++i) Bx[i] = i < na ? F[i] : 0.0;
   if (mode == EL_RECOVER) {
     for (int i = 0; i < 3; ++i)
@@ -745,7 +749,7 @@ HDI void element_cached(const QuadTables& Q, const CellGeom& g, int mode, const 
       if (c == 0) {
         btx = Bx[na + i * m + j];
       } else {
-        btx = 0.0;
+        btx = nx ? (*nx)[na + i * m + j] : 0.0;  // load on the facet unknown's test rows
         for (int a = 0; a < na; ++a) btx -= fac[oHta + (long)(i * m + j) * na + a] * Bx[a];
       }
       out[l1] = btx;

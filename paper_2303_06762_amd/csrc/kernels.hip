@@ -48,8 +48,9 @@ __global__ void k_load(ElemLevel E, int c0, int nbatch, const double* __restrict
   double nuc = E.nu_per_cell ? E.nu[c] : E.nu[0];
   double* out = gK + (long)c * nK;
   if (E.fac) {
+    const WS nx{E.nw_load ? E.nw_load + c : nullptr, E.nc};
     element_cached(E.Q, g, EL_LOAD, f + (long)c * E.Q.nq * 2, nullptr, 0.0, WS{E.fac + c, E.nc},
-                   WS{ws + t, nbatch}, out);
+                   WS{ws + t, nbatch}, out, E.nw_load ? &nx : nullptr);
   } else {
     int rc = element_local(E.Q, g, nuc, E.beta, 0.0, EL_LOAD, f + (long)c * E.Q.nq * 2, nullptr, 0.0,
                            WS{ws + t, nbatch}, out, nullptr, nullptr, E.CT,
@@ -88,8 +89,9 @@ __global__ void k_recover(ElemLevel E, int c0, int nbatch, const double* __restr
   double out[3 * NQ_MAX];
   double nuc = E.nu_per_cell ? E.nu[c] : E.nu[0];
   if (E.fac) {
+    const WS nx{E.nw_load ? E.nw_load + c : nullptr, E.nc};
     element_cached(E.Q, g, EL_RECOVER, f + (long)c * E.Q.nq * 2, lk, p0[c], WS{E.fac + c, E.nc},
-                   WS{ws + t, nbatch}, out);
+                   WS{ws + t, nbatch}, out, E.nw_load ? &nx : nullptr);
   } else {
     int rc = element_local(E.Q, g, nuc, E.beta, 0.0, EL_RECOVER, f + (long)c * E.Q.nq * 2, lk, p0[c],
                            WS{ws + t, nbatch}, out, nullptr, nullptr, E.CT,

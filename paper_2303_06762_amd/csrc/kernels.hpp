@@ -46,6 +46,12 @@ struct ElemLevel {
                             // of cell c at fac[i * nc + c]), or null
   int nc;
   int transpose;            // 1: cells of the transposed (adjoint) system (with a wind)
+  // Newton linearisation (order-k level, with a wind): the previous state's
+  // skeleton vector [N_skel] and the per-cell Newton load written by the
+  // condensation (element i of cell c at nw_load[i * nc + c], nz entries:
+  // RT rows then tangential facet rows); both null for Picard / Stokes
+  const double* nw_lam;
+  double* nw_load;
 };
 
 void launch_condense(hipStream_t st, const ElemLevel& E, int c0, int nbatch, double* ws, double* S, int* status);

@@ -197,6 +197,11 @@ struct hdgmg_ctx {
   double *fdiv = nullptr, *cdiv = nullptr, *area = nullptr;
   double* gK = nullptr;
   double* statebuf = nullptr;  // [N_skel + n_cells] for hdgmg_solve without state
+  // Newton linearisation: the previous state's skeleton vector and the
+  // per-cell Newton loads (allocated at the first hdgmg_set_newton)
+  bool has_newton = false;
+  double* nw_lam = nullptr;
+  double* nw_load = nullptr;
   // adjoint solve buffers (allocated at the first hdgmg_solve_adjoint)
   double* adj_f = nullptr;      // [n_cells][n_q][2] adjoint source values
   double* adj_p = nullptr;      // [n_cells][n_q] adjoint pressure
@@ -1286,6 +1291,9 @@ ElemLevel elem_level(const hdgmg_ctx* ctx, const DevLevel& D, bool order_k, bool
   E.fac = order_k ? ctx->fac : nullptr;
   E.nc = D.nc;
   E.transpose = E.CT && ctx->opts.transpose ? 1 : 0;
+  const bool nw = order_k && E.CT && ctx->has_newton;
+  E.nw_lam = nw ? ctx->nw_lam : nullptr;
+  E.nw_load = nw ? ctx->nw_load : nullptr;
   return E;
 }
 
@@ -1714,6 +1722,7 @@ hdgmg_status hdgmg_set_wind(hdgmg_ctx* ctx, const double* w_qp) {
   drop_graph(ctx);
   ctx->assembled = false;
   ctx->has_wind = false;
+  ctx->has_newton = false;  // a Newton state belongs to the wind it came with
   if (!w_qp) return HDGMG_OK;
   hipStream_t st = ctx->st;
   DevLevel& KL = ctx->K;
@@ -1766,6 +1775,34 @@ hdgmg_status hdgmg_set_wind(hdgmg_ctx* ctx, const double* w_qp) {
   TRY(check_status(ctx, "lowest-order wind"));
   HIPC(hipStreamSynchronize(st));
   ctx->has_wind = true;
+  return HDGMG_OK;
+}
+
+hdgmg_status hdgmg_set_newton(hdgmg_ctx* ctx, const double* state_prev) {
+  if (!ctx) return HDGMG_EINVAL;
+  if (!state_prev) {
+    if (ctx->has_newton) {
+      drop_graph(ctx);
+      ctx->assembled = false;
+    }
+    ctx->has_newton = false;
+    return HDGMG_OK;
+  }
+  if (!ctx->opts.oseen || ctx->opts.transpose || ctx->k < 1 || !ctx->has_wind) {
+    ctx->err = "hdgmg_set_newton needs an opts.oseen context (not transposed), k >= 1 and a wind";
+    return HDGMG_ESTATE;
+  }
+  const DevLevel& KL = ctx->K;
+  if (!ctx->nw_lam) {
+    TRY(dalloc(ctx, &ctx->nw_lam, (size_t)std::max<long>(KL.ndof, 1)));
+    TRY(dalloc(ctx, &ctx->nw_load, (size_t)KL.nc * dims_of(ctx->k).nz));
+  }
+  drop_graph(ctx);
+  ctx->assembled = false;
+  if (KL.ndof > 0) launch_copy(ctx->st, KL.ndof, state_prev, ctx->nw_lam);
+  HIPC(hipGetLastError());
+  HIPC(hipStreamSynchronize(ctx->st));
+  ctx->has_newton = true;
   return HDGMG_OK;
 }
 
