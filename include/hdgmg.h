@@ -87,7 +87,10 @@ typedef struct {
   double rtol, atol;       /* inner stop: ||r||_2 <= max(rtol ||r0||_2, atol) */
   int max_it;              /* inner iteration cap                          */
   int uzawa_max;           /* AL-Uzawa step cap                            */
-  double uzawa_tol;        /* stop when ||p_n - p_{n-1}||_L2 <= tol*max(1,||p_n||) */
+  double uzawa_tol;        /* stop when ||p_n - p_{n-1}||_L2 <= tol*max(1,||p_n||);
+                              < 0: exactly uzawa_max steps (the paper's fixed
+                              count at large eps^-1), not reported as
+                              NOT_CONVERGED                                */
   int coarse_dofs;         /* lowest-order levels with at most this many
                               unknowns run MG_h inside one single-workgroup
                               kernel (0: every level launch by launch)     */
@@ -234,14 +237,19 @@ hdgmg_status hdgmg_solve_adjoint(hdgmg_ctx* ctx, const double* f_qp, const doubl
                                  const double* gu_qp, double* gf_qp, double* gnu,
                                  double* adj_state, hdgmg_info* info);
 
-/* hdgmg_solve from an initial skeleton iterate: x0 (device, N_skel, may be
- * NULL for zero) starts the first inner solve of the AL-Uzawa iteration;
- * for Picard steps (Sec. 4.2) it is the previous step's skeleton vector
- * (state[0 .. N_skel)).  With opts.oseen every later inner solve starts
- * from the latest iterate; the Stokes path starts every inner solve from
- * zero.  x0 may alias state. */
+/* hdgmg_solve from an initial iterate: x0 (device, N_skel, may be NULL for
+ * zero) starts the first inner solve of the AL-Uzawa iteration; for Picard
+ * and Newton steps (Sec. 4.2) it is the previous step's skeleton vector
+ * (state[0 .. N_skel)).  p_init (device, n_cells, may be NULL for zero) is
+ * the initial piecewise-constant pressure p^(0) of the AL-Uzawa loop: zero
+ * for the Picard form (nsOpEq-ALU); the previous pressure for a Newton
+ * step, which makes the loop on (u_n, p_n) the paper's loop on the
+ * increments (du, dp) from (0, 0).  With opts.oseen every later inner solve
+ * starts from the latest iterate; the Stokes path starts every inner solve
+ * from zero.  x0 and p_init may alias state. */
 hdgmg_status hdgmg_solve_x0(hdgmg_ctx* ctx, const double* f_qp, const double* x0,
-                            double* u_qp, double* p_qp, double* state, hdgmg_info* info);
+                            const double* p_init, double* u_qp, double* p_qp,
+                            double* state, hdgmg_info* info);
 
 /* Wind of the Picard-linearised convection (Sec. 4.2: the previous
  * velocity), given by its values at the data points, w_qp device

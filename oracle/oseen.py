@@ -440,9 +440,13 @@ class OseenSetup:
         self.restart = restart
 
     def solve(self, f_qp, lam0=None, rtol=1e-8, atol=1e-10, max_it=500, uzawa_max=50,
-              uzawa_tol=1e-10):
+              uzawa_tol=1e-10, p_init=None):
+        """p_init: the initial pressure of the AL-Uzawa loop (zero for the
+        Picard form; the previous pressure for a Newton step, which makes
+        the loop on (u_n, p_n) the paper's loop on the increments from
+        zero).  uzawa_tol < 0: exactly uzawa_max steps."""
         g = self.prob.rhs(f_qp)
-        p = np.zeros(self.lv.n_cells)
+        p = np.zeros(self.lv.n_cells) if p_init is None else p_init.copy()
         lam = np.zeros(self.prob.n_dof) if lam0 is None else lam0.copy()
         log = []
         area = self.lv.area
@@ -505,14 +509,16 @@ def l2_diff(prob, u1, u2):
 
 
 def picard_newton(levels, k, nu, beta, gamma, f_qp, dirichlet=None, eps_picard=1e-4, newton_rtol=1e-8,
-                  newton_atol=1e-10, max_picard=50, max_newton=20, direct=False, **kw):
+                  newton_atol=1e-10, max_picard=50, max_newton=20, direct=False, solve_kw=None, **kw):
     """Alg. 3: a Stokes solve, Picard steps until ||u_n - u_{n-1}||_0 <
     eps_picard, then Newton steps until ||u_n - u_{n-1}||_0 <=
     max(newton_rtol ||u_n||_0, newton_atol); every step starts from the
-    previous skeleton vector.  Returns the per-step dicts (kind, lam, p0, u,
-    its, du)."""
+    previous skeleton vector, a Newton step's AL-Uzawa loop from the
+    previous pressure.  solve_kw: options of OseenSetup.solve.  Returns the
+    per-step dicts (kind, lam, p0, u, its, du)."""
     out = []
-    winds = zs = lam = u_prev = None
+    solve_kw = solve_kw or {}
+    winds = zs = lam = u_prev = p_prev = None
     kind = "stokes"
     n_p = n_n = 0
     while True:
@@ -525,7 +531,7 @@ def picard_newton(levels, k, nu, beta, gamma, f_qp, dirichlet=None, eps_picard=1
         else:
             S = OseenSetup(levels, k, nu, beta, gamma, winds, dirichlet, newton_z=nz_, **kw)
             prob = S.prob
-            r = S.solve(f_qp, lam0=lam)
+            r = S.solve(f_qp, lam0=lam, p_init=p_prev if kind == "newton" else None, **solve_kw)
         u, _, _, _ = prob.recover(r["lam"], r["p0"], f_qp)
         du = None if u_prev is None else l2_diff(prob, u, u_prev)
         r.update(kind=kind, u=u, du=du, setup=S, prob=prob)
@@ -544,5 +550,5 @@ def picard_newton(levels, k, nu, beta, gamma, f_qp, dirichlet=None, eps_picard=1
                 kind = "picard"
         winds = state_wind(prob, r["lam"], r["p0"], f_qp)
         zs = local_states(prob, r["lam"], f_qp)
-        lam, u_prev = r["lam"], u
+        lam, u_prev, p_prev = r["lam"], u, r["p0"]
     return out

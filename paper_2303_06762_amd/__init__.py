@@ -9,6 +9,8 @@ import ctypes
 import os
 import sys
 
+_IS_FINALIZING = sys.is_finalizing
+
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -106,7 +108,7 @@ def lib():
     L.hdgmg_solve.restype = i32
     L.hdgmg_solve_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(Info)]
     L.hdgmg_solve_adjoint.restype = i32
-    L.hdgmg_solve_x0.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(Info)]
+    L.hdgmg_solve_x0.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(Info)]
     L.hdgmg_solve_x0.restype = i32
     for name in ("hdgmg_set_wind", "hdgmg_set_newton", "hdgmg_set_dirichlet"):
         getattr(L, name).argtypes = [vp, vp]
@@ -202,9 +204,9 @@ class Solver:
     def __del__(self):
         # at interpreter exit the process releases the device memory; the
         # allocator callbacks must not run into a half torn-down torch
-        if sys.is_finalizing():
-            return
         try:
+            if _IS_FINALIZING():
+                return
             self.close()
         except Exception:
             pass
@@ -253,15 +255,18 @@ class Solver:
         self._check(lib().hdgmg_recover(self._h, _ptr(f_qp), _ptr(state), _ptr(u), _ptr(p)))
         return u, p
 
-    def solve(self, f_qp, x0=None):
+    def solve(self, f_qp, x0=None, p_init=None):
         """Returns (u_qp, p_qp, state, info dict, status).  x0: initial
-        skeleton iterate (N_skel), e.g. state[:n_skel] of a previous solve."""
+        skeleton iterate (N_skel), e.g. state[:n_skel] of a previous solve;
+        p_init: initial P0 pressure of the AL-Uzawa loop (n_cells), e.g.
+        state[n_skel:] of the previous state for a Newton step."""
         u = self.torch.empty((self.n_cells, self.n_q, 2), dtype=self.torch.float64, device="cuda")
         p = self.torch.empty((self.n_cells, self.n_q), dtype=self.torch.float64, device="cuda")
         state = self._vec(self.n_skel + self.n_cells)
         info = Info()
         x0p = ctypes.c_void_p(None) if x0 is None else _ptr(x0)
-        st = self._check(lib().hdgmg_solve_x0(self._h, _ptr(f_qp), x0p, _ptr(u), _ptr(p), _ptr(state),
+        pip = ctypes.c_void_p(None) if p_init is None else _ptr(p_init)
+        st = self._check(lib().hdgmg_solve_x0(self._h, _ptr(f_qp), x0p, pip, _ptr(u), _ptr(p), _ptr(state),
                                               ctypes.byref(info)), allow=(0, 1))
         n = info.uzawa_steps
         d = dict(uzawa_steps=n, its=list(info.its[:n]), rel_res=list(info.rel_res[:n]),
@@ -429,8 +434,10 @@ def picard_newton(solver, f_qp, dirichlet=None, eps_picard=1e-4, newton_rtol=1e-
     """Alg. 3 on an opts.oseen Solver: a Stokes solve, Picard steps until
     ||u_n - u_{n-1}||_0 < eps_picard, then Newton steps until
     ||u_n - u_{n-1}||_0 <= max(newton_rtol ||u_n||_0, newton_atol); every
-    step starts from the previous skeleton vector.  Returns a list of dicts
-    (kind, u, p, state, info, status, du) per solve."""
+    step starts from the previous skeleton vector, and a Newton step's
+    AL-Uzawa loop from the previous pressure (the paper's loop on the
+    increments from zero).  Returns a list of dicts (kind, u, p, state,
+    info, status, du) per solve."""
     torch = solver.torch
     W = solver.data_weights()
 
@@ -443,9 +450,9 @@ def picard_newton(solver, f_qp, dirichlet=None, eps_picard=1e-4, newton_rtol=1e-
     solver.assemble()
     out = []
     kind, n_p, n_n = "stokes", 0, 0
-    x0 = None
+    x0 = p_init = None
     while True:
-        u, p, state, info, st = solver.solve(f_qp, x0=x0)
+        u, p, state, info, st = solver.solve(f_qp, x0=x0, p_init=p_init if kind == "newton" else None)
         du = None if not out else l2(u - out[-1]["u"])
         out.append(dict(kind=kind, u=u, p=p, state=state, info=info, status=st, du=du))
         if kind == "newton":
@@ -462,5 +469,5 @@ def picard_newton(solver, f_qp, dirichlet=None, eps_picard=1e-4, newton_rtol=1e-
         if kind == "newton":
             solver.set_newton(state)
         solver.assemble()
-        x0 = state[:solver.n_skel]
+        x0, p_init = state[:solver.n_skel], state[solver.n_skel:]
     return out

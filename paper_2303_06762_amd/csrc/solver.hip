@@ -1832,11 +1832,11 @@ hdgmg_status hdgmg_recover(hdgmg_ctx* ctx, const double* f_qp, const double* sta
 
 hdgmg_status hdgmg_solve(hdgmg_ctx* ctx, const double* f_qp, double* u_qp, double* p_qp, double* state,
                          hdgmg_info* info) {
-  return hdgmg_solve_x0(ctx, f_qp, nullptr, u_qp, p_qp, state, info);
+  return hdgmg_solve_x0(ctx, f_qp, nullptr, nullptr, u_qp, p_qp, state, info);
 }
 
-hdgmg_status hdgmg_solve_x0(hdgmg_ctx* ctx, const double* f_qp, const double* x0, double* u_qp, double* p_qp,
-                            double* state, hdgmg_info* info) {
+hdgmg_status hdgmg_solve_x0(hdgmg_ctx* ctx, const double* f_qp, const double* x0, const double* p_init,
+                            double* u_qp, double* p_qp, double* state, hdgmg_info* info) {
   if (!ctx || !f_qp || !u_qp || !p_qp) return HDGMG_EINVAL;
   if (!ctx->assembled) {
     ctx->err = "hdgmg_solve before hdgmg_assemble";
@@ -1850,8 +1850,12 @@ hdgmg_status hdgmg_solve_x0(hdgmg_ctx* ctx, const double* f_qp, const double* x0
     launch_copy(st, KL.ndof, x0, ctx->lam);
   else
     launch_fill(st, KL.ndof, 0.0, ctx->lam);
+  // p^(0) before the load: p_init may alias the caller's state
+  if (p_init)
+    launch_copy(st, KL.nc, p_init, ctx->p0);
+  else
+    launch_fill(st, KL.nc, 0.0, ctx->p0);
   TRY(hdgmg_rhs(ctx, f_qp, ctx->gvec));
-  launch_fill(st, KL.nc, 0.0, ctx->p0);
   hdgmg_status result = HDGMG_OK;
   for (int n = 0; n < ctx->opts.uzawa_max; ++n) {
     launch_uzawa_rhs(st, KL.nint, KL.m, ctx->gvec, ctx->fdiv, KL.fcell, ctx->p0, ctx->b);
@@ -1877,7 +1881,7 @@ hdgmg_status hdgmg_solve_x0(hdgmg_ctx* ctx, const double* f_qp, const double* x0
       info->div_l2 = dn / ctx->gamma;
     }
     if (dn <= ctx->opts.uzawa_tol * std::max(1.0, pn)) break;
-    if (n == ctx->opts.uzawa_max - 1) {
+    if (n == ctx->opts.uzawa_max - 1 && ctx->opts.uzawa_tol >= 0) {
       result = HDGMG_NOT_CONVERGED;
       ctx->err = "AL-Uzawa reached uzawa_max";
     }
