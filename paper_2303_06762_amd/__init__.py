@@ -372,36 +372,88 @@ def _make_function():
 
         @staticmethod
         def forward(ctx, solver, f_qp, nu):
-            us, states = [], []
-            for f in f_qp:
-                f = f.contiguous()
-                u, _, state, _, _ = solver.solve(f)
-                us.append(u)
-                states.append(state)
-            ctx.solver = solver
-            ctx.save_for_backward(f_qp, torch.stack(states))
-            return torch.stack(us)
+            pool = list(solver) if isinstance(solver, (list, tuple)) else [solver]
+            f_qp = f_qp.contiguous()
+
+            def run(s, idx):
+                return [s.solve(f_qp[i])[:3] for i in idx]
+
+            res = _over_pool(pool, f_qp.shape[0], run)
+            us = torch.stack([r[0] for r in res])
+            states = torch.stack([r[2] for r in res])
+            torch.cuda.synchronize()
+            ctx.pool = pool
+            ctx.save_for_backward(f_qp, states)
+            return us
 
         @staticmethod
         def backward(ctx, gu):
             f_qp, states = ctx.saved_tensors
-            solver = ctx.solver
-            gnu = torch.zeros(solver.n_cells, dtype=torch.float64, device=f_qp.device)
-            gfs = []
-            for i in range(f_qp.shape[0]):
-                gf, _, _, _, _ = solver.solve_adjoint(f_qp[i].contiguous(), states[i], gu[i].contiguous(),
-                                                      gnu=gnu)
-                gfs.append(gf)
-            return None, torch.stack(gfs), gnu
+            pool = ctx.pool
+            gu = gu.contiguous()
+            # one viscosity-gradient accumulator per solver (per stream)
+            gnus = [torch.zeros(s.n_cells, dtype=torch.float64, device=f_qp.device) for s in pool]
+
+            def run(s, idx):
+                g = gnus[pool.index(s)]
+                return [s.solve_adjoint(f_qp[i], states[i], gu[i], gnu=g)[0] for i in idx]
+
+            gfs = _over_pool(pool, f_qp.shape[0], run)
+            gf = torch.stack(gfs)
+            gnu = torch.stack(gnus).sum(dim=0)
+            torch.cuda.synchronize()
+            return None, gf, gnu
 
     return StokesSolve
+
+
+def _over_pool(pool, n, run):
+    """Right-hand sides 0..n-1 dealt round-robin over the solvers of `pool`
+    (one context per HIP stream), each solver's share run by a host thread
+    of its own with its stream current (the library calls release the
+    interpreter lock), so that independent solves overlap on the device.
+    Returns the n results in order."""
+    import torch
+    shares = [list(range(j, n, len(pool))) for j in range(len(pool))]
+    # inputs (and zeroed accumulators) come from the caller's stream
+    torch.cuda.synchronize()
+
+    def work(j):
+        s = pool[j]
+        with torch.cuda.stream(s.stream):
+            return run(s, shares[j])
+
+    if len(pool) == 1:
+        outs = [work(0)]
+    else:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(max_workers=len(pool)) as ex:
+            outs = list(ex.map(work, range(len(pool))))
+    res = [None] * n
+    for j, idx in enumerate(shares):
+        for i, r in zip(idx, outs[j]):
+            res[i] = r
+    return res
+
+
+def solver_pool(n, coords, cells, n_refine, k, beta, nu, gamma, **kw):
+    """n identical, assembled Solvers, each on a HIP stream of its own
+    (default priority), for stokes_solve over a batch of sources."""
+    import torch
+    pool = [Solver(coords, cells, n_refine, k, beta, nu, gamma, stream=torch.cuda.Stream(), **kw)
+            for _ in range(n)]
+    for s in pool:
+        s.assemble()
+    return pool
 
 
 _STOKES_SOLVE = None
 
 
 def stokes_solve(solver, f_qp, nu):
-    """Differentiable batched solve: u_qp = stokes_solve(solver, f_qp, nu)."""
+    """Differentiable batched solve: u_qp = stokes_solve(solver, f_qp, nu).
+    solver: an assembled Solver, or a list of identical ones (solver_pool)
+    over which the batch is spread so that the solves run concurrently."""
     global _STOKES_SOLVE
     if _STOKES_SOLVE is None:
         _STOKES_SOLVE = _make_function()

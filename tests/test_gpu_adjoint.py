@@ -153,3 +153,38 @@ def test_adjoint_identities_at_128x128(beta):
         e_rhs = -float((gu * u).sum())
         assert abs(e_lhs - e_rhs) <= 1e-6 * abs(e_rhs)
     s.close()
+
+
+def test_stream_pool_batch_matches_single_solver():
+    # the batch spread over four contexts on four HIP streams (solves
+    # running concurrently) gives the single context's results
+    import paper_2303_06762_amd as hd
+    c, t = synth.kuhn_square(4)
+    nr, k, beta, gamma = 1, 2, 1.0, 1e2
+    n_cells = 32 * 4 ** nr
+    nu = lognormal_nu(n_cells)
+    nq = (k + 2) ** 2
+    nrhs = 6
+    F = synth.source_uniform(100, nrhs, n_cells, nq)
+    ut = dev(synth.source_uniform(4, 1, n_cells, nq)[0])
+    _note("stream pool: 6 sources over 4 streams")
+    s = hd.Solver(c, t, nr, k, beta, nu, gamma)
+    s.assemble()
+    W = s.data_weights()
+    pool = hd.solver_pool(4, c, t, nr, k, beta, nu, gamma)
+    res = []
+    for solver in (s, pool):
+        f_t = dev(F).requires_grad_(True)
+        nu_t = dev(nu).requires_grad_(True)
+        u = hd.stokes_solve(solver, f_t, nu_t)
+        J = (W[None, :, :, None] * (u - ut[None]) ** 2).sum()
+        J.backward()
+        res.append((host(u), J.item(), host(f_t.grad), host(nu_t.grad)))
+    (u0, J0, gf0, gn0), (u1, J1, gf1, gn1) = res
+    assert np.abs(u1 - u0).max() <= 1e-12 * np.abs(u0).max()
+    assert abs(J1 - J0) <= 1e-12 * abs(J0)
+    assert np.abs(gf1 - gf0).max() <= 1e-12 * np.abs(gf0).max()
+    assert np.abs(gn1 - gn0).max() <= 1e-12 * np.abs(gn0).max()
+    for p_ in pool:
+        p_.close()
+    s.close()
