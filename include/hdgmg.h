@@ -124,11 +124,22 @@ typedef struct {
                               and the coarsest inverse are then those of
                               A^T): the adjoint of the Oseen system, used
                               by hdgmg_solve_adjoint; 0: the system itself */
+  int coarse_dense;        /* 1 (V-cycle only): at assembly MG_h on the top
+                              level of the single-workgroup kernel (levels
+                              0..Lc, from a zero iterate, with the sweep
+                              count the V-cycle uses there) is tabulated as
+                              a dense matrix -- the kernel applied to the
+                              columns of the identity, a workgroup per
+                              column -- and each V-cycle applies it by one
+                              GEMV instead of running the kernel (the same
+                              linear operator up to rounding); 0: the
+                              kernel runs in every V-cycle              */
 } hdgmg_opts;
 
 /* Defaults: m_p = m_h = 1, V-cycle, growth 2, rtol 1e-8, atol 1e-10,
  * max_it 500, uzawa_max 50, uzawa_tol 1e-10, coarse_dofs 2048,
- * stream_dofs 65536, vcycle_precision 0, oseen 0, restart 50, transpose 0. */
+ * stream_dofs 65536, vcycle_precision 0, oseen 0, restart 50, transpose 0,
+ * coarse_dense 1. */
 void hdgmg_default_opts(hdgmg_opts* opts);
 
 #define HDGMG_MAX_UZAWA 64

@@ -34,7 +34,8 @@ class Opts(ctypes.Structure):
                 ("atol", ctypes.c_double), ("max_it", ctypes.c_int), ("uzawa_max", ctypes.c_int),
                 ("uzawa_tol", ctypes.c_double), ("coarse_dofs", ctypes.c_int),
                 ("stream_dofs", ctypes.c_int), ("vcycle_precision", ctypes.c_int),
-                ("oseen", ctypes.c_int), ("restart", ctypes.c_int), ("transpose", ctypes.c_int)]
+                ("oseen", ctypes.c_int), ("restart", ctypes.c_int), ("transpose", ctypes.c_int),
+                ("coarse_dense", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):

@@ -183,7 +183,9 @@ __device__ void smooth(const CoarseLevel& Ld, const char* lds, const int* bitem,
 
 template <int NS, typename TS>
 __global__ void __launch_bounds__(CT) k_coarse_cycle(const CoarseLevel* __restrict__ Lg, int top, int m_top,
-                                                     int growth, int q, const TS* __restrict__ inv0, int n0) {
+                                                     int growth, int q, const TS* __restrict__ inv0, int n0,
+                                                     const double* __restrict__ g_top, double* u_top,
+                                                     long bstride) {
   extern __shared__ double smem[];
   __shared__ CoarseLevel Ls[COARSE_MAX_LEVELS];
   __shared__ int sbitem[COARSE_MAX_LEVELS][COARSE_MAX_BATCH + 1];
@@ -209,9 +211,12 @@ __global__ void __launch_bounds__(CT) k_coarse_cycle(const CoarseLevel* __restri
     const CoarseLevel& T = Ls[top];
     double* u = smem + T.off_u;
     double* g = smem + T.off_g;
+    // top-level vectors: the level's own, or column blockIdx.x of a batch
+    const double* gsrc = g_top ? g_top + blockIdx.x * bstride : T.g_glob;
+    const double* usrc = g_top ? u_top + blockIdx.x * bstride : T.u_glob;
     for (int i = tid; i < T.n; i += CT) {
-      u[i] = gmem(T.u_glob)[i];
-      g[i] = gmem(T.g_glob)[i];
+      u[i] = gmem(usrc)[i];
+      g[i] = gmem(gsrc)[i];
     }
   }
   __syncthreads();
@@ -291,7 +296,8 @@ __global__ void __launch_bounds__(CT) k_coarse_cycle(const CoarseLevel* __restri
   {
     const CoarseLevel& T = Ls[top];
     const double* u = smem + T.off_u;
-    for (int i = tid; i < T.n; i += CT) T.u_glob[i] = u[i];
+    double* udst = g_top ? u_top + blockIdx.x * bstride : T.u_glob;
+    for (int i = tid; i < T.n; i += CT) udst[i] = u[i];
   }
 }
 
@@ -392,13 +398,16 @@ void launch_gs_records(hipStream_t st, const unsigned* meta, const void* val, co
 
 template <typename TS>
 void coarse_t(hipStream_t st, const CoarseLevel* Ls, int top, int m_top, int growth, int q, const TS* inv0,
-              int n0, int ns_max, size_t shm) {
+              int n0, int ns_max, size_t shm, int nb, const double* g_top, double* u_top, long bstride) {
   if (ns_max <= 12)
-    hipLaunchKernelGGL((k_coarse_cycle<12, TS>), dim3(1), dim3(CT), shm, st, Ls, top, m_top, growth, q, inv0, n0);
+    hipLaunchKernelGGL((k_coarse_cycle<12, TS>), dim3(nb), dim3(CT), shm, st, Ls, top, m_top, growth, q, inv0, n0,
+                       g_top, u_top, bstride);
   else if (ns_max <= 16)
-    hipLaunchKernelGGL((k_coarse_cycle<16, TS>), dim3(1), dim3(CT), shm, st, Ls, top, m_top, growth, q, inv0, n0);
+    hipLaunchKernelGGL((k_coarse_cycle<16, TS>), dim3(nb), dim3(CT), shm, st, Ls, top, m_top, growth, q, inv0, n0,
+                       g_top, u_top, bstride);
   else
-    hipLaunchKernelGGL((k_coarse_cycle<32, TS>), dim3(1), dim3(CT), shm, st, Ls, top, m_top, growth, q, inv0, n0);
+    hipLaunchKernelGGL((k_coarse_cycle<32, TS>), dim3(nb), dim3(CT), shm, st, Ls, top, m_top, growth, q, inv0, n0,
+                       g_top, u_top, bstride);
 }
 
 template <typename TS>
@@ -421,11 +430,20 @@ size_t coarse_cycle_static_lds() {
 
 void launch_coarse_cycle(hipStream_t st, const CoarseLevel* Ls, int top, int m_top, int growth, int q,
                          const void* inv0, int n0, int ns_max, int lds_doubles, int f32) {
+  launch_coarse_cycle_batch(st, Ls, top, m_top, growth, q, inv0, n0, ns_max, lds_doubles, f32, 1, nullptr,
+                            nullptr, 0);
+}
+
+void launch_coarse_cycle_batch(hipStream_t st, const CoarseLevel* Ls, int top, int m_top, int growth, int q,
+                               const void* inv0, int n0, int ns_max, int lds_doubles, int f32, int nb,
+                               const double* g_top, double* u_top, long bstride) {
+  if (nb <= 0) return;
   size_t shm = sizeof(double) * (size_t)lds_doubles;
   if (f32)
-    coarse_t<float>(st, Ls, top, m_top, growth, q, (const float*)inv0, n0, ns_max, shm);
+    coarse_t<float>(st, Ls, top, m_top, growth, q, (const float*)inv0, n0, ns_max, shm, nb, g_top, u_top, bstride);
   else
-    coarse_t<double>(st, Ls, top, m_top, growth, q, (const double*)inv0, n0, ns_max, shm);
+    coarse_t<double>(st, Ls, top, m_top, growth, q, (const double*)inv0, n0, ns_max, shm, nb, g_top, u_top,
+                     bstride);
 }
 
 }  // namespace hdgmg

@@ -79,5 +79,14 @@ hipError_t prepare_coarse_cycle(int ns_max, size_t lds_bytes, int f32);
 size_t coarse_cycle_static_lds();
 void launch_coarse_cycle(hipStream_t st, const CoarseLevel* Ls, int top, int m_top, int growth, int q,
                          const void* inv0, int n0, int ns_max, int lds_doubles, int f32);
+// The same cycle for nb independent top-level right-hand sides, a workgroup
+// each: workgroup b reads g_top + b*bstride and u_top + b*bstride (the
+// initial iterate) and writes the result to u_top + b*bstride; the level
+// descriptors' own top-level vectors are not touched.  With g_top the
+// columns of the identity and u_top zero this tabulates MG_h on the top
+// level as a dense matrix (column j = MG_h(e_j)).
+void launch_coarse_cycle_batch(hipStream_t st, const CoarseLevel* Ls, int top, int m_top, int growth, int q,
+                               const void* inv0, int n0, int ns_max, int lds_doubles, int f32, int nb,
+                               const double* g_top, double* u_top, long bstride);
 
 }  // namespace hdgmg

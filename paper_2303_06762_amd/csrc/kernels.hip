@@ -585,6 +585,38 @@ __global__ void k_gemv_dense(int n, const TS* __restrict__ A, const double* __re
   y[r] = s;
 }
 
+// y = A x for a dense row-major A (n x n, storage TS), a wavefront per row:
+// the lanes stride the row with coalesced loads, FP64 accumulation, then a
+// wavefront reduction.
+template <typename TS>
+__global__ void __launch_bounds__(256) k_gemv_rows(int n, const TS* __restrict__ A, const double* __restrict__ x,
+                                                   double* __restrict__ y) {
+  const int lane = threadIdx.x & 63;
+  const long row = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= n) return;
+  const TS* a = A + row * n;
+  double s = 0.0;
+  for (int j = lane; j < n; j += 64) s += (double)a[j] * x[j];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if (lane == 0) y[row] = s;
+}
+
+// out (row-major, storage TS) = transpose of the column-major in (n x n)
+template <typename TS>
+__global__ void k_transpose_to(int n, const double* __restrict__ in, TS* __restrict__ out) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)n * n) return;
+  const long i = t / n, j = t % n;  // out[i][j] = in column j, row i
+  out[t] = (TS)in[j * n + i];
+}
+
+// columns of the n x n identity (column-major)
+__global__ void k_identity(int n, double* __restrict__ out) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)n * n) return;
+  out[t] = (t / n == t % n) ? 1.0 : 0.0;
+}
+
 __global__ void k_to_f32(long n, const double* __restrict__ in, float* __restrict__ out) {
   long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t < n) out[t] = (float)in[t];
@@ -850,6 +882,23 @@ template <typename TS>
 void launch_gemv_dense(hipStream_t st, int n, const TS* A, const double* x, double* y) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_gemv_dense<TS>, dim3(nblk(n)), dim3(TPB), 0, st, n, A, x, y);
+}
+template <typename TS>
+void launch_gemv_rows(hipStream_t st, int n, const TS* A, const double* x, double* y) {
+  if (n > 0) hipLaunchKernelGGL(k_gemv_rows<TS>, dim3((n + 3) / 4), dim3(256), 0, st, n, A, x, y);
+}
+template void launch_gemv_rows<double>(hipStream_t, int, const double*, const double*, double*);
+template void launch_gemv_rows<float>(hipStream_t, int, const float*, const double*, double*);
+template <typename TS>
+void launch_transpose_to(hipStream_t st, int n, const double* in, TS* out) {
+  const long nn = (long)n * n;
+  if (nn > 0) hipLaunchKernelGGL(k_transpose_to<TS>, dim3(nblk(nn)), dim3(TPB), 0, st, n, in, out);
+}
+template void launch_transpose_to<double>(hipStream_t, int, const double*, double*);
+template void launch_transpose_to<float>(hipStream_t, int, const double*, float*);
+void launch_identity(hipStream_t st, int n, double* out) {
+  const long nn = (long)n * n;
+  if (nn > 0) hipLaunchKernelGGL(k_identity, dim3(nblk(nn)), dim3(TPB), 0, st, n, out);
 }
 template void launch_gemv_dense<double>(hipStream_t, int, const double*, const double*, double*);
 template void launch_gemv_dense<float>(hipStream_t, int, const float*, const double*, double*);

@@ -197,6 +197,12 @@ struct hdgmg_ctx {
   double *fdiv = nullptr, *cdiv = nullptr, *area = nullptr;
   double* gK = nullptr;
   double* statebuf = nullptr;  // [N_skel + n_cells] for hdgmg_solve without state
+  // MG_h on the coarse kernel's top level tabulated as a dense row-major
+  // matrix (storage of the V-cycle precision), applied by one GEMV when the
+  // cycle enters that level from zero with dense_m sweeps
+  bool dense_on = false;
+  void* dense_M = nullptr;
+  int dense_n = 0, dense_m = 0;
   // Newton linearisation: the previous state's skeleton vector and the
   // per-cell Newton loads (allocated at the first hdgmg_set_newton)
   bool has_newton = false;
@@ -628,6 +634,16 @@ void mg_h(hdgmg_ctx* ctx, int l, int m_l, bool u_zero) {
   if (l <= ctx->Lc) {
     int t = kt_begin(ctx, 4);
     const bool f32 = vc_f32(ctx);
+    if (ctx->dense_on && l == ctx->Lc && u_zero && m_l == ctx->dense_m) {
+      // u = MG_h(l, g, 0): the tabulated operator
+      const int n = ctx->dense_n;
+      if (f32)
+        launch_gemv_rows<float>(ctx->st, n, (const float*)ctx->dense_M, D.g, D.u);
+      else
+        launch_gemv_rows<double>(ctx->st, n, (const double*)ctx->dense_M, D.g, D.u);
+      kt_end(ctx, 4, t, (double)n * n * (f32 ? 4.0 : 8.0) + 2.0 * n * 8.0);
+      return;
+    }
     launch_coarse_cycle(ctx->st, ctx->coarse_desc, l, m_l, ctx->opts.vcycle_growth, ctx->opts.cycle,
                         f32 ? (const void*)ctx->coarse_inv32 : (const void*)ctx->coarse_inv, ctx->n0,
                         ctx->coarse_ns, ctx->coarse_lds, f32 ? 1 : 0);
@@ -1268,6 +1284,63 @@ hdgmg_status build_record_levels(hdgmg_ctx* ctx) {
 
 // Element data of a level for the local solver kernels.  wind: with the
 // level's wind coefficients (order-k: ctx->wcoef; lowest order: D.wcoef).
+// Tabulate u = MG_h(Lc, g, 0) (Alg. 1 on levels 0..Lc, the V-cycle's sweep
+// count there) as a dense matrix: the single-workgroup kernel applied to the
+// columns of the identity, a workgroup per column, then stored row-major in
+// the V-cycle's storage precision.  The V-cycle (q = 1) enters level Lc
+// from a zero iterate once per application, so one GEMV replaces the
+// kernel's sequence of dependent colour phases by a bandwidth-bound read.
+hdgmg_status build_dense_coarse(hdgmg_ctx* ctx) {
+  ctx->dense_on = false;
+  ctx->dense_M = nullptr;
+  if (!ctx->opts.coarse_dense || ctx->opts.cycle != 1 || ctx->Lc < 1) return HDGMG_OK;
+  const int Lc = ctx->Lc;
+  const int n = 2 * ctx->lv[Lc].nint;
+  int m = ctx->opts.m_smooth;
+  for (int l = ctx->J - 1; l > Lc; --l) m *= ctx->opts.vcycle_growth;
+  const bool f32 = vc_f32(ctx);
+  const size_t nn = (size_t)n * n;
+  double* G = (double*)dmalloc(ctx, nn * sizeof(double));
+  double* U = (double*)dmalloc(ctx, nn * sizeof(double));
+  if (!G || !U) {
+    dfree(ctx, G);
+    dfree(ctx, U);
+    ctx->err = "device allocation for the dense coarse operator failed";
+    return HDGMG_ENOMEM;
+  }
+  hipStream_t st = ctx->st;
+  launch_identity(st, n, G);
+  launch_fill(st, (long)nn, 0.0, U);
+  launch_coarse_cycle_batch(st, ctx->coarse_desc, Lc, m, ctx->opts.vcycle_growth, 1,
+                            f32 ? (const void*)ctx->coarse_inv32 : (const void*)ctx->coarse_inv, ctx->n0,
+                            ctx->coarse_ns, ctx->coarse_lds, f32 ? 1 : 0, n, G, U, n);
+  hdgmg_status s = HDGMG_OK;
+  if (f32) {
+    float* M = nullptr;
+    s = dalloc(ctx, &M, nn);
+    if (!s) launch_transpose_to<float>(st, n, U, M);
+    ctx->dense_M = M;
+  } else {
+    double* M = nullptr;
+    s = dalloc(ctx, &M, nn);
+    if (!s) launch_transpose_to<double>(st, n, U, M);
+    ctx->dense_M = M;
+  }
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  dfree(ctx, G);
+  dfree(ctx, U);
+  if (s) return s;
+  if (e != hipSuccess) {
+    ctx->err = std::string("HIP error: ") + hipGetErrorString(e) + " in the coarse tabulation";
+    return HDGMG_EHIP;
+  }
+  ctx->dense_n = n;
+  ctx->dense_m = m;
+  ctx->dense_on = true;
+  return HDGMG_OK;
+}
+
 ElemLevel elem_level(const hdgmg_ctx* ctx, const DevLevel& D, bool order_k, bool wind) {
   ElemLevel E;
   E.Q = order_k ? ctx->Q : ctx->Q0;
@@ -1362,6 +1435,7 @@ hdgmg_status assemble_levels(hdgmg_ctx* ctx) {
     TRY(make_f32(ctx, D));
   }
   TRY(build_coarse(ctx));
+  TRY(build_dense_coarse(ctx));
   TRY(build_record_levels(ctx));
   HIPC(hipStreamSynchronize(ctx->st));
   return HDGMG_OK;
@@ -1388,6 +1462,7 @@ void hdgmg_default_opts(hdgmg_opts* o) {
   o->oseen = 0;
   o->restart = 50;
   o->transpose = 0;
+  o->coarse_dense = 1;
 }
 
 const char* hdgmg_last_error(const hdgmg_ctx* ctx) {
@@ -1451,7 +1526,8 @@ hdgmg_status hdgmg_setup(const hdgmg_mesh* mesh, int k, double beta, const doubl
       ctx->opts.uzawa_max > HDGMG_MAX_UZAWA || !(ctx->opts.rtol >= 0) || !(ctx->opts.atol >= 0) ||
       ctx->opts.vcycle_precision < 0 || ctx->opts.vcycle_precision > 2 || ctx->opts.oseen < 0 ||
       ctx->opts.oseen > 1 || ctx->opts.restart < 1 || ctx->opts.restart > 64 || ctx->opts.transpose < 0 ||
-      ctx->opts.transpose > 1 || (ctx->opts.transpose && !ctx->opts.oseen)) {
+      ctx->opts.transpose > 1 || (ctx->opts.transpose && !ctx->opts.oseen) || ctx->opts.coarse_dense < 0 ||
+      ctx->opts.coarse_dense > 1) {
     g_setup_error = "invalid options";
     delete ctx;
     return HDGMG_EINVAL;
@@ -1639,7 +1715,14 @@ hdgmg_status hdgmg_assemble(hdgmg_ctx* ctx) {
       v += 2.0 * K.ndof * 8.0;                                                 // the mode-0 transfers
     }
     double visits = 1.0, m_l = o.m_smooth;
+    bool dense_done = false;
     for (int l = ctx->J - 1; l >= 1; --l) {
+      if (ctx->dense_on && l == ctx->Lc) {
+        // levels 0..Lc: one read of the tabulated operator
+        v += (double)ctx->dense_n * ctx->dense_n * (o.vcycle_precision >= 1 ? 4.0 : 8.0) + 2.0 * ctx->dense_n * 8.0;
+        dense_done = true;
+        break;
+      }
       const DevLevel& D = ctx->cr[l];
       double sw = 0.0;
       for (int c = 0; c < (int)D.colour_ptr.size() - 1; ++c) sw += phase_bytes(ctx, D, l, c);
@@ -1652,7 +1735,7 @@ hdgmg_status hdgmg_assemble(hdgmg_ctx* ctx) {
       visits *= o.cycle;
       m_l *= o.vcycle_growth;
     }
-    v += visits * (double)ctx->n0 * ctx->n0 * (o.vcycle_precision >= 1 ? 4.0 : 8.0);
+    if (!dense_done) v += visits * (double)ctx->n0 * ctx->n0 * (o.vcycle_precision >= 1 ? 4.0 : 8.0);
     ctx->vcycle_bytes = v;
   }
   ctx->assembled = true;

@@ -36,7 +36,7 @@ _ORACLES = {}
 
 
 def oracle_setup(key, coords, cells, n_refine, k, nu, beta, gamma, **kw):
-    kw = {a: b for a, b in kw.items() if a not in ("coarse_dofs", "stream_dofs")}  # layout only
+    kw = {a: b for a, b in kw.items() if a not in ("coarse_dofs", "stream_dofs", "coarse_dense")}  # layout only
     if key not in _ORACLES:
         _ORACLES[key] = solver.Setup(coords, cells, n_refine, k, nu, beta, gamma, **kw)
     return _ORACLES[key]
@@ -81,6 +81,11 @@ CASES = {
     "k1_per_level": (lambda: synth.kuhn_square(4), 2, 1, 1.0, 1.0, 1e2, dict(coarse_dofs=0)),
     # levels 0-1 in the single-workgroup kernel, level 2 launched
     "k2_split": (lambda: synth.kuhn_square(4), 2, 2, 1.0, 1.0, 1e2, dict(coarse_dofs=400)),
+    # the single-workgroup kernel in every V-cycle (its top level not
+    # tabulated as a dense operator)
+    "k2_kernel_coarse": (lambda: synth.kuhn_square(4), 2, 2, 1.0, 1.0, 1e2, dict(coarse_dense=0)),
+    "k1_split_kernel_coarse": (lambda: synth.kuhn_square(2), 3, 1, 1.0, 1.0, 1e2,
+                               dict(coarse_dofs=400, coarse_dense=0)),
     "wcycle_split": (lambda: synth.kuhn_square(2), 3, 1, 1.0, 1.0, 1e2,
                      dict(q=2, growth=1, coarse_dofs=400)),
     # streaming cell-apply / patch-relax kernels on every level
