@@ -586,17 +586,31 @@ __global__ void k_gemv_dense(int n, const TS* __restrict__ A, const double* __re
 }
 
 // y = A x for a dense row-major A (n x n, storage TS), a wavefront per row:
-// the lanes stride the row with coalesced loads, FP64 accumulation, then a
-// wavefront reduction.
+// the lanes stride the row with coalesced loads, sixteen of them issued
+// before any is used (one memory round trip per 1024 entries), FP64
+// accumulation, then a wavefront reduction.
 template <typename TS>
 __global__ void __launch_bounds__(256) k_gemv_rows(int n, const TS* __restrict__ A, const double* __restrict__ x,
                                                    double* __restrict__ y) {
+  constexpr int U = 16;
   const int lane = threadIdx.x & 63;
   const long row = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= n) return;
   const TS* a = A + row * n;
   double s = 0.0;
-  for (int j = lane; j < n; j += 64) s += (double)a[j] * x[j];
+  for (int j0 = 0; j0 < n; j0 += 64 * U) {
+    TS av[U];
+    double xv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int j = j0 + 64 * u + lane;
+      const bool ok = j < n;
+      av[u] = ok ? a[j] : (TS)0;
+      xv[u] = ok ? x[j] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) s += (double)av[u] * xv[u];
+  }
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
   if (lane == 0) y[row] = s;
 }
