@@ -181,11 +181,14 @@ __device__ void smooth(const CoarseLevel& Ld, const char* lds, const int* bitem,
   }
 }
 
-template <int NS, typename TS>
+// GT: the top level's vectors u, g, r live in memory (column blockIdx.x of
+// g_top / u_top / r_top, stride bstride) instead of LDS -- a level too large
+// for LDS, used when MG_h on it is tabulated; the lower levels stay in LDS.
+template <int NS, typename TS, bool GT>
 __global__ void __launch_bounds__(CT) k_coarse_cycle(const CoarseLevel* __restrict__ Lg, int top, int m_top,
                                                      int growth, int q, const TS* __restrict__ inv0, int n0,
                                                      const double* __restrict__ g_top, double* u_top,
-                                                     long bstride) {
+                                                     double* r_top, long bstride) {
   extern __shared__ double smem[];
   __shared__ CoarseLevel Ls[COARSE_MAX_LEVELS];
   __shared__ int sbitem[COARSE_MAX_LEVELS][COARSE_MAX_BATCH + 1];
@@ -207,7 +210,7 @@ __global__ void __launch_bounds__(CT) k_coarse_cycle(const CoarseLevel* __restri
     if (L.lds_val >= 0) copy_to_lds((char*)smem + L.lds_val, L.it_val, (COARSE_NNZ + G - 1) / G * nit);
     if (L.lds_ainv >= 0) copy_to_lds((char*)smem + L.lds_ainv, L.it_ainv, (L.ns_max + G - 1) / G * nit);
   }
-  {
+  if constexpr (!GT) {
     const CoarseLevel& T = Ls[top];
     double* u = smem + T.off_u;
     double* g = smem + T.off_g;
@@ -246,6 +249,11 @@ __global__ void __launch_bounds__(CT) k_coarse_cycle(const CoarseLevel* __restri
     double* u = smem + L.off_u;
     double* g = smem + L.off_g;
     double* r = smem + L.off_r;
+    if (GT && l == top) {
+      u = u_top + blockIdx.x * bstride;
+      g = const_cast<double*>(g_top) + blockIdx.x * bstride;
+      r = r_top + blockIdx.x * bstride;
+    }
     double* ub = smem + B.off_u;
     double* gb = smem + B.off_g;
     if (state[l] == 0) {
@@ -293,7 +301,7 @@ __global__ void __launch_bounds__(CT) k_coarse_cycle(const CoarseLevel* __restri
     if (l == top) break;
     ++l;
   }
-  {
+  if constexpr (!GT) {
     const CoarseLevel& T = Ls[top];
     const double* u = smem + T.off_u;
     double* udst = g_top ? u_top + blockIdx.x * bstride : T.u_glob;
@@ -396,28 +404,36 @@ void launch_gs_records(hipStream_t st, const unsigned* meta, const void* val, co
     gs_records_t<double>(st, m, (const double*)val, (const double*)ainv, nit, nsm, b0, nb, u, g);
 }
 
-template <typename TS>
+template <typename TS, bool GT>
 void coarse_t(hipStream_t st, const CoarseLevel* Ls, int top, int m_top, int growth, int q, const TS* inv0,
-              int n0, int ns_max, size_t shm, int nb, const double* g_top, double* u_top, long bstride) {
+              int n0, int ns_max, size_t shm, int nb, const double* g_top, double* u_top, double* r_top,
+              long bstride) {
   if (ns_max <= 12)
-    hipLaunchKernelGGL((k_coarse_cycle<12, TS>), dim3(nb), dim3(CT), shm, st, Ls, top, m_top, growth, q, inv0, n0,
-                       g_top, u_top, bstride);
+    hipLaunchKernelGGL((k_coarse_cycle<12, TS, GT>), dim3(nb), dim3(CT), shm, st, Ls, top, m_top, growth, q, inv0,
+                       n0, g_top, u_top, r_top, bstride);
   else if (ns_max <= 16)
-    hipLaunchKernelGGL((k_coarse_cycle<16, TS>), dim3(nb), dim3(CT), shm, st, Ls, top, m_top, growth, q, inv0, n0,
-                       g_top, u_top, bstride);
+    hipLaunchKernelGGL((k_coarse_cycle<16, TS, GT>), dim3(nb), dim3(CT), shm, st, Ls, top, m_top, growth, q, inv0,
+                       n0, g_top, u_top, r_top, bstride);
   else
-    hipLaunchKernelGGL((k_coarse_cycle<32, TS>), dim3(nb), dim3(CT), shm, st, Ls, top, m_top, growth, q, inv0, n0,
-                       g_top, u_top, bstride);
+    hipLaunchKernelGGL((k_coarse_cycle<32, TS, GT>), dim3(nb), dim3(CT), shm, st, Ls, top, m_top, growth, q, inv0,
+                       n0, g_top, u_top, r_top, bstride);
 }
 
+template <typename TS, bool GT>
+hipError_t prepare_tg(int ns_max, int v) {
+  if (ns_max <= 12)
+    return hipFuncSetAttribute((const void*)k_coarse_cycle<12, TS, GT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               v);
+  if (ns_max <= 16)
+    return hipFuncSetAttribute((const void*)k_coarse_cycle<16, TS, GT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               v);
+  return hipFuncSetAttribute((const void*)k_coarse_cycle<32, TS, GT>, hipFuncAttributeMaxDynamicSharedMemorySize, v);
+}
 template <typename TS>
 hipError_t prepare_t(int ns_max, size_t lds_bytes) {
   const int v = (int)lds_bytes;
-  if (ns_max <= 12)
-    return hipFuncSetAttribute((const void*)k_coarse_cycle<12, TS>, hipFuncAttributeMaxDynamicSharedMemorySize, v);
-  if (ns_max <= 16)
-    return hipFuncSetAttribute((const void*)k_coarse_cycle<16, TS>, hipFuncAttributeMaxDynamicSharedMemorySize, v);
-  return hipFuncSetAttribute((const void*)k_coarse_cycle<32, TS>, hipFuncAttributeMaxDynamicSharedMemorySize, v);
+  hipError_t e = prepare_tg<TS, false>(ns_max, v);
+  return e != hipSuccess ? e : prepare_tg<TS, true>(ns_max, v);
 }
 
 hipError_t prepare_coarse_cycle(int ns_max, size_t lds_bytes, int f32) {
@@ -431,19 +447,29 @@ size_t coarse_cycle_static_lds() {
 void launch_coarse_cycle(hipStream_t st, const CoarseLevel* Ls, int top, int m_top, int growth, int q,
                          const void* inv0, int n0, int ns_max, int lds_doubles, int f32) {
   launch_coarse_cycle_batch(st, Ls, top, m_top, growth, q, inv0, n0, ns_max, lds_doubles, f32, 1, nullptr,
-                            nullptr, 0);
+                            nullptr, nullptr, 0);
 }
 
 void launch_coarse_cycle_batch(hipStream_t st, const CoarseLevel* Ls, int top, int m_top, int growth, int q,
                                const void* inv0, int n0, int ns_max, int lds_doubles, int f32, int nb,
-                               const double* g_top, double* u_top, long bstride) {
+                               const double* g_top, double* u_top, double* r_top, long bstride) {
   if (nb <= 0) return;
   size_t shm = sizeof(double) * (size_t)lds_doubles;
-  if (f32)
-    coarse_t<float>(st, Ls, top, m_top, growth, q, (const float*)inv0, n0, ns_max, shm, nb, g_top, u_top, bstride);
-  else
-    coarse_t<double>(st, Ls, top, m_top, growth, q, (const double*)inv0, n0, ns_max, shm, nb, g_top, u_top,
-                     bstride);
+  if (r_top) {
+    if (f32)
+      coarse_t<float, true>(st, Ls, top, m_top, growth, q, (const float*)inv0, n0, ns_max, shm, nb, g_top, u_top,
+                            r_top, bstride);
+    else
+      coarse_t<double, true>(st, Ls, top, m_top, growth, q, (const double*)inv0, n0, ns_max, shm, nb, g_top, u_top,
+                             r_top, bstride);
+  } else {
+    if (f32)
+      coarse_t<float, false>(st, Ls, top, m_top, growth, q, (const float*)inv0, n0, ns_max, shm, nb, g_top, u_top,
+                             nullptr, bstride);
+    else
+      coarse_t<double, false>(st, Ls, top, m_top, growth, q, (const double*)inv0, n0, ns_max, shm, nb, g_top,
+                              u_top, nullptr, bstride);
+  }
 }
 
 }  // namespace hdgmg

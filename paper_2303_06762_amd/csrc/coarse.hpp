@@ -84,9 +84,12 @@ void launch_coarse_cycle(hipStream_t st, const CoarseLevel* Ls, int top, int m_t
 // initial iterate) and writes the result to u_top + b*bstride; the level
 // descriptors' own top-level vectors are not touched.  With g_top the
 // columns of the identity and u_top zero this tabulates MG_h on the top
-// level as a dense matrix (column j = MG_h(e_j)).
+// level as a dense matrix (column j = MG_h(e_j)).  r_top non-null: the top
+// level's vectors stay in memory (u_top, g_top and the residual r_top, each
+// column at b*bstride), for a top level too large for LDS (its descriptor's
+// LDS offsets are ignored).
 void launch_coarse_cycle_batch(hipStream_t st, const CoarseLevel* Ls, int top, int m_top, int growth, int q,
                                const void* inv0, int n0, int ns_max, int lds_doubles, int f32, int nb,
-                               const double* g_top, double* u_top, long bstride);
+                               const double* g_top, double* u_top, double* r_top, long bstride);
 
 }  // namespace hdgmg

@@ -202,7 +202,10 @@ struct hdgmg_ctx {
   // cycle enters that level from zero with dense_m sweeps
   bool dense_on = false;
   void* dense_M = nullptr;
-  int dense_n = 0, dense_m = 0;
+  int dense_n = 0, dense_m = 0, dense_level = -1;
+  // level Lc + 1 described to the coarse kernel with its vectors in memory,
+  // only for the tabulation (-1: none)
+  int Lt = -1;
   // Newton linearisation: the previous state's skeleton vector and the
   // per-cell Newton loads (allocated at the first hdgmg_set_newton)
   bool has_newton = false;
@@ -255,6 +258,9 @@ namespace {
 
 // Device memory through the caller's allocator when one was given at setup
 // (e.g. PyTorch's caching allocator), else hipMalloc / hipFree.
+// Largest level (unknowns) whose MG_h is tabulated as a dense matrix.
+constexpr int DENSE_MAX_N = 8192;
+
 void* dmalloc(hdgmg_ctx* ctx, size_t bytes) {
   if (ctx->alloc_fn) return ctx->alloc_fn(bytes, ctx->alloc_ctx);
   void* v = nullptr;
@@ -631,19 +637,21 @@ void apply_k(hdgmg_ctx* ctx, const double* x, double* y, double alpha, const dou
 // u_l is zero on entry.
 void mg_h(hdgmg_ctx* ctx, int l, int m_l, bool u_zero) {
   DevLevel& D = ctx->cr[l];
+  if (ctx->dense_on && l == ctx->dense_level && u_zero && m_l == ctx->dense_m) {
+    // u = MG_h(l, g, 0): the tabulated operator
+    int t = kt_begin(ctx, 4);
+    const bool f32 = vc_f32(ctx);
+    const int n = ctx->dense_n;
+    if (f32)
+      launch_gemv_rows<float>(ctx->st, n, (const float*)ctx->dense_M, D.g, D.u);
+    else
+      launch_gemv_rows<double>(ctx->st, n, (const double*)ctx->dense_M, D.g, D.u);
+    kt_end(ctx, 4, t, (double)n * n * (f32 ? 4.0 : 8.0) + 2.0 * n * 8.0);
+    return;
+  }
   if (l <= ctx->Lc) {
     int t = kt_begin(ctx, 4);
     const bool f32 = vc_f32(ctx);
-    if (ctx->dense_on && l == ctx->Lc && u_zero && m_l == ctx->dense_m) {
-      // u = MG_h(l, g, 0): the tabulated operator
-      const int n = ctx->dense_n;
-      if (f32)
-        launch_gemv_rows<float>(ctx->st, n, (const float*)ctx->dense_M, D.g, D.u);
-      else
-        launch_gemv_rows<double>(ctx->st, n, (const double*)ctx->dense_M, D.g, D.u);
-      kt_end(ctx, 4, t, (double)n * n * (f32 ? 4.0 : 8.0) + 2.0 * n * 8.0);
-      return;
-    }
     launch_coarse_cycle(ctx->st, ctx->coarse_desc, l, m_l, ctx->opts.vcycle_growth, ctx->opts.cycle,
                         f32 ? (const void*)ctx->coarse_inv32 : (const void*)ctx->coarse_inv, ctx->n0,
                         ctx->coarse_ns, ctx->coarse_lds, f32 ? 1 : 0);
@@ -675,9 +683,12 @@ void mg_h(hdgmg_ctx* ctx, int l, int m_l, bool u_zero) {
 
 // Alg. 2 with zero initial guess: z = MG_hp(r)
 void mg_hp_body(hdgmg_ctx* ctx, const double* r, double* z);
+// Per-kernel timers (every class but the whole-cycle one, 3) bracket each
+// launch with events, so the cycle then runs eagerly; the whole-cycle timer
+// alone brackets the graph replay.
 bool timers_on(const hdgmg_ctx* ctx) {
-  for (const auto& T : ctx->timers)
-    if (T.on) return true;
+  for (int c = 0; c < (int)(sizeof(ctx->timers) / sizeof(ctx->timers[0])); ++c)
+    if (c != 3 && ctx->timers[c].on) return true;
   return false;
 }
 
@@ -1214,6 +1225,57 @@ hdgmg_status build_coarse(hdgmg_ctx* ctx) {
     C.P_ci = T.Pe_ci;
     C.P_v = f32 ? (const void*)T.Pe_v32 : (const void*)T.Pe_v;
   }
+  // The next level, vectors in memory, for the tabulation of MG_h on it
+  // (V-cycle with coarse_dense only; its operator must stay a modest dense
+  // matrix)
+  ctx->Lt = -1;
+  if (ctx->opts.coarse_dense && ctx->opts.cycle == 1 && Lc + 1 < ctx->J && Lc + 1 < COARSE_MAX_LEVELS &&
+      2 * ctx->lv[Lc + 1].nint <= DENSE_MAX_N && 2 * ctx->lv[Lc + 1].max_patch_facets <= 32 && Lc >= 1) {
+    const int l = Lc + 1;
+    const Level& L = ctx->lv[l];
+    DevLevel& D = ctx->cr[l];
+    CoarseLevel C;
+    std::memset(&C, 0, sizeof(C));
+    C.n = 2 * L.nint;
+    C.off_u = C.off_g = C.off_r = 0;
+    C.u_glob = D.u;
+    C.g_glob = D.g;
+    C.lds_meta = C.lds_val = C.lds_ainv = -1;
+    LevelRecords R;
+    TRY(level_records(ctx, l, COARSE_THREADS, R));
+    C.ncol = L.ncol;
+    C.nitems = R.nit;
+    C.ns_max = R.nsm;
+    C.nbatch = (int)R.bitem.size() - 1;
+    if (C.nbatch <= COARSE_MAX_BATCH) {
+      int* ti;
+      unsigned* tu;
+      TRY(upload(ctx, &ti, R.bwd));
+      C.bseq_bwd = ti;
+      TRY(upload(ctx, &tu, R.meta));
+      C.it_meta = (const uint4*)tu;
+      TRY(upload(ctx, &ti, R.cb));
+      C.cb_ptr = ti;
+      TRY(upload(ctx, &ti, R.bitem));
+      C.bitem = ti;
+      TRY(upload_vals(ctx, R.val, &C.it_val));
+      TRY(upload_vals(ctx, R.ainv, &C.it_ainv));
+      TRY(upload_vals(ctx, R.rw_val, &C.rw_val));
+      TRY(upload(ctx, &ti, R.rw_col));
+      C.rw_col = ti;
+      const bool f32 = vc_f32(ctx);
+      const DevTransfer& T = ctx->tr[l];
+      C.R_w = T.Rw;
+      C.R_ci = T.Re_ci;
+      C.R_v = f32 ? (const void*)T.Re_v32 : (const void*)T.Re_v;
+      C.P_w = T.Pw;
+      C.P_ci = T.Pe_ci;
+      C.P_v = f32 ? (const void*)T.Pe_v32 : (const void*)T.Pe_v;
+      desc.push_back(C);
+      nsmax = std::max(nsmax, 2 * L.max_patch_facets);
+      ctx->Lt = l;
+    }
+  }
   // Record parts that stay in LDS for the whole kernel, coarsest levels
   // first (they have the most sweeps): residual rows before inverse rows.
   {
@@ -1294,26 +1356,31 @@ hdgmg_status build_dense_coarse(hdgmg_ctx* ctx) {
   ctx->dense_on = false;
   ctx->dense_M = nullptr;
   if (!ctx->opts.coarse_dense || ctx->opts.cycle != 1 || ctx->Lc < 1) return HDGMG_OK;
-  const int Lc = ctx->Lc;
-  const int n = 2 * ctx->lv[Lc].nint;
+  // the level whose MG_h is tabulated: Lc + 1 (vectors in memory) when the
+  // coarse kernel describes it, else Lc
+  const int Ld = ctx->Lt >= 0 ? ctx->Lt : ctx->Lc;
+  const bool gtop = ctx->Lt >= 0;
+  const int n = 2 * ctx->lv[Ld].nint;
   int m = ctx->opts.m_smooth;
-  for (int l = ctx->J - 1; l > Lc; --l) m *= ctx->opts.vcycle_growth;
+  for (int l = ctx->J - 1; l > Ld; --l) m *= ctx->opts.vcycle_growth;
   const bool f32 = vc_f32(ctx);
   const size_t nn = (size_t)n * n;
   double* G = (double*)dmalloc(ctx, nn * sizeof(double));
   double* U = (double*)dmalloc(ctx, nn * sizeof(double));
-  if (!G || !U) {
+  double* Rw = gtop ? (double*)dmalloc(ctx, nn * sizeof(double)) : nullptr;
+  if (!G || !U || (gtop && !Rw)) {
     dfree(ctx, G);
     dfree(ctx, U);
+    dfree(ctx, Rw);
     ctx->err = "device allocation for the dense coarse operator failed";
     return HDGMG_ENOMEM;
   }
   hipStream_t st = ctx->st;
   launch_identity(st, n, G);
   launch_fill(st, (long)nn, 0.0, U);
-  launch_coarse_cycle_batch(st, ctx->coarse_desc, Lc, m, ctx->opts.vcycle_growth, 1,
+  launch_coarse_cycle_batch(st, ctx->coarse_desc, Ld, m, ctx->opts.vcycle_growth, 1,
                             f32 ? (const void*)ctx->coarse_inv32 : (const void*)ctx->coarse_inv, ctx->n0,
-                            ctx->coarse_ns, ctx->coarse_lds, f32 ? 1 : 0, n, G, U, n);
+                            ctx->coarse_ns, ctx->coarse_lds, f32 ? 1 : 0, n, G, U, Rw, n);
   hdgmg_status s = HDGMG_OK;
   if (f32) {
     float* M = nullptr;
@@ -1330,6 +1397,7 @@ hdgmg_status build_dense_coarse(hdgmg_ctx* ctx) {
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   dfree(ctx, G);
   dfree(ctx, U);
+  dfree(ctx, Rw);
   if (s) return s;
   if (e != hipSuccess) {
     ctx->err = std::string("HIP error: ") + hipGetErrorString(e) + " in the coarse tabulation";
@@ -1337,6 +1405,7 @@ hdgmg_status build_dense_coarse(hdgmg_ctx* ctx) {
   }
   ctx->dense_n = n;
   ctx->dense_m = m;
+  ctx->dense_level = Ld;
   ctx->dense_on = true;
   return HDGMG_OK;
 }
@@ -1717,7 +1786,7 @@ hdgmg_status hdgmg_assemble(hdgmg_ctx* ctx) {
     double visits = 1.0, m_l = o.m_smooth;
     bool dense_done = false;
     for (int l = ctx->J - 1; l >= 1; --l) {
-      if (ctx->dense_on && l == ctx->Lc) {
+      if (ctx->dense_on && l == ctx->dense_level) {
         // levels 0..Lc: one read of the tabulated operator
         v += (double)ctx->dense_n * ctx->dense_n * (o.vcycle_precision >= 1 ? 4.0 : 8.0) + 2.0 * ctx->dense_n * 8.0;
         dense_done = true;
