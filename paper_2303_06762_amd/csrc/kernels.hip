@@ -585,43 +585,62 @@ __global__ void k_gemv_dense(int n, const TS* __restrict__ A, const double* __re
   y[r] = s;
 }
 
-// y = A x for a dense row-major A (n x n, storage TS), a wavefront per row:
-// the lanes stride the row with coalesced loads, sixteen of them issued
-// before any is used (one memory round trip per 1024 entries), FP64
-// accumulation, then a wavefront reduction.
+// y = A x for a dense row-major A (n x n, storage TS, row stride ld: a
+// multiple of 4, zero-padded), a wavefront per row: each lane reads four
+// consecutive entries per 16-byte load (two for FP64), eight such loads in
+// flight before any is used, FP64 accumulation, then a wavefront reduction.
 template <typename TS>
-__global__ void __launch_bounds__(256) k_gemv_rows(int n, const TS* __restrict__ A, const double* __restrict__ x,
-                                                   double* __restrict__ y) {
-  constexpr int U = 16;
+__global__ void __launch_bounds__(256) k_gemv_rows(int n, int ld, const TS* __restrict__ A,
+                                                   const double* __restrict__ x, double* __restrict__ y) {
+  constexpr int U = 8;
   const int lane = threadIdx.x & 63;
   const long row = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= n) return;
-  const TS* a = A + row * n;
+  const TS* a = A + row * ld;
   double s = 0.0;
-  for (int j0 = 0; j0 < n; j0 += 64 * U) {
-    TS av[U];
-    double xv[U];
+  for (int j0 = 0; j0 < ld; j0 += 4 * 64 * U) {
+    TS av[U][4];
+    double xv[U][4];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int j = j0 + 64 * u + lane;
-      const bool ok = j < n;
-      av[u] = ok ? a[j] : (TS)0;
-      xv[u] = ok ? x[j] : 0.0;
+      const int j = j0 + 4 * (64 * u + lane);
+      if (j < ld) {
+        if constexpr (sizeof(TS) == 4) {
+          const float4 v = *(const float4*)(a + j);
+          av[u][0] = v.x, av[u][1] = v.y, av[u][2] = v.z, av[u][3] = v.w;
+        } else {
+          const double2 v0 = *(const double2*)(a + j), v1 = *(const double2*)(a + j + 2);
+          av[u][0] = v0.x, av[u][1] = v0.y, av[u][2] = v1.x, av[u][3] = v1.y;
+        }
+      } else {
+        av[u][0] = av[u][1] = av[u][2] = av[u][3] = (TS)0;
+      }
+      // x with the matrix entries (the padding columns past n read nothing)
+      if (j + 3 < n) {
+        const double2 x0 = *(const double2*)(x + j), x1 = *(const double2*)(x + j + 2);
+        xv[u][0] = x0.x, xv[u][1] = x0.y, xv[u][2] = x1.x, xv[u][3] = x1.y;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) xv[u][e] = j + e < n ? x[j + e] : 0.0;
+      }
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u) s += (double)av[u] * xv[u];
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) s += (double)av[u][e] * xv[u][e];
   }
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
   if (lane == 0) y[row] = s;
 }
 
-// out (row-major, storage TS) = transpose of the column-major in (n x n)
+// out (row-major, storage TS, row stride ld >= n, padding zeroed) = the
+// transpose of the column-major n x n matrix in
 template <typename TS>
-__global__ void k_transpose_to(int n, const double* __restrict__ in, TS* __restrict__ out) {
+__global__ void k_transpose_to(int n, int ld, const double* __restrict__ in, TS* __restrict__ out) {
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (long)n * n) return;
-  const long i = t / n, j = t % n;  // out[i][j] = in column j, row i
-  out[t] = (TS)in[j * n + i];
+  if (t >= (long)n * ld) return;
+  const long i = t / ld, j = t % ld;  // out[i][j] = in column j, row i
+  out[t] = j < n ? (TS)in[j * n + i] : (TS)0;
 }
 
 // columns of the n x n identity (column-major)
@@ -898,18 +917,18 @@ void launch_gemv_dense(hipStream_t st, int n, const TS* A, const double* x, doub
   hipLaunchKernelGGL(k_gemv_dense<TS>, dim3(nblk(n)), dim3(TPB), 0, st, n, A, x, y);
 }
 template <typename TS>
-void launch_gemv_rows(hipStream_t st, int n, const TS* A, const double* x, double* y) {
-  if (n > 0) hipLaunchKernelGGL(k_gemv_rows<TS>, dim3((n + 3) / 4), dim3(256), 0, st, n, A, x, y);
+void launch_gemv_rows(hipStream_t st, int n, int ld, const TS* A, const double* x, double* y) {
+  if (n > 0) hipLaunchKernelGGL(k_gemv_rows<TS>, dim3((n + 3) / 4), dim3(256), 0, st, n, ld, A, x, y);
 }
-template void launch_gemv_rows<double>(hipStream_t, int, const double*, const double*, double*);
-template void launch_gemv_rows<float>(hipStream_t, int, const float*, const double*, double*);
+template void launch_gemv_rows<double>(hipStream_t, int, int, const double*, const double*, double*);
+template void launch_gemv_rows<float>(hipStream_t, int, int, const float*, const double*, double*);
 template <typename TS>
-void launch_transpose_to(hipStream_t st, int n, const double* in, TS* out) {
-  const long nn = (long)n * n;
-  if (nn > 0) hipLaunchKernelGGL(k_transpose_to<TS>, dim3(nblk(nn)), dim3(TPB), 0, st, n, in, out);
+void launch_transpose_to(hipStream_t st, int n, int ld, const double* in, TS* out) {
+  const long nn = (long)n * ld;
+  if (nn > 0) hipLaunchKernelGGL(k_transpose_to<TS>, dim3(nblk(nn)), dim3(TPB), 0, st, n, ld, in, out);
 }
-template void launch_transpose_to<double>(hipStream_t, int, const double*, double*);
-template void launch_transpose_to<float>(hipStream_t, int, const double*, float*);
+template void launch_transpose_to<double>(hipStream_t, int, int, const double*, double*);
+template void launch_transpose_to<float>(hipStream_t, int, int, const double*, float*);
 void launch_identity(hipStream_t st, int n, double* out) {
   const long nn = (long)n * n;
   if (nn > 0) hipLaunchKernelGGL(k_identity, dim3(nblk(nn)), dim3(TPB), 0, st, n, out);

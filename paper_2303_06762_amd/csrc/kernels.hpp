@@ -115,12 +115,14 @@ void launch_ell_spmv(hipStream_t st, int n, int w, const int* ci, const TS* v, c
                      double beta_y, double* zero_out = nullptr);
 template <typename TS>
 void launch_gemv_dense(hipStream_t st, int n, const TS* A, const double* x, double* y);
-// y = A x, A dense row-major n x n in storage TS (a wavefront per row)
+// y = A x, A dense row-major n x n in storage TS with row stride ld (a
+// multiple of 4, rows zero-padded; a wavefront per row, 16-byte loads)
 template <typename TS>
-void launch_gemv_rows(hipStream_t st, int n, const TS* A, const double* x, double* y);
-// out (row-major, TS) = transpose of the column-major n x n matrix in
+void launch_gemv_rows(hipStream_t st, int n, int ld, const TS* A, const double* x, double* y);
+// out (row-major, TS, row stride ld, padding zeroed) = transpose of the
+// column-major n x n matrix in
 template <typename TS>
-void launch_transpose_to(hipStream_t st, int n, const double* in, TS* out);
+void launch_transpose_to(hipStream_t st, int n, int ld, const double* in, TS* out);
 // the n x n identity, column-major
 void launch_identity(hipStream_t st, int n, double* out);
 void launch_fill(hipStream_t st, long n, double v, double* x);

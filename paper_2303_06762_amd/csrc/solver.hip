@@ -202,7 +202,7 @@ struct hdgmg_ctx {
   // cycle enters that level from zero with dense_m sweeps
   bool dense_on = false;
   void* dense_M = nullptr;
-  int dense_n = 0, dense_m = 0, dense_level = -1;
+  int dense_n = 0, dense_ld = 0, dense_m = 0, dense_level = -1;
   // level Lc + 1 described to the coarse kernel with its vectors in memory,
   // only for the tabulation (-1: none)
   int Lt = -1;
@@ -643,9 +643,9 @@ void mg_h(hdgmg_ctx* ctx, int l, int m_l, bool u_zero) {
     const bool f32 = vc_f32(ctx);
     const int n = ctx->dense_n;
     if (f32)
-      launch_gemv_rows<float>(ctx->st, n, (const float*)ctx->dense_M, D.g, D.u);
+      launch_gemv_rows<float>(ctx->st, n, ctx->dense_ld, (const float*)ctx->dense_M, D.g, D.u);
     else
-      launch_gemv_rows<double>(ctx->st, n, (const double*)ctx->dense_M, D.g, D.u);
+      launch_gemv_rows<double>(ctx->st, n, ctx->dense_ld, (const double*)ctx->dense_M, D.g, D.u);
     kt_end(ctx, 4, t, (double)n * n * (f32 ? 4.0 : 8.0) + 2.0 * n * 8.0);
     return;
   }
@@ -1382,17 +1382,19 @@ hdgmg_status build_dense_coarse(hdgmg_ctx* ctx) {
                             f32 ? (const void*)ctx->coarse_inv32 : (const void*)ctx->coarse_inv, ctx->n0,
                             ctx->coarse_ns, ctx->coarse_lds, f32 ? 1 : 0, n, G, U, Rw, n);
   hdgmg_status s = HDGMG_OK;
+  const int ld = (n + 3) / 4 * 4;  // rows start on 16-byte boundaries
   if (f32) {
     float* M = nullptr;
-    s = dalloc(ctx, &M, nn);
-    if (!s) launch_transpose_to<float>(st, n, U, M);
+    s = dalloc(ctx, &M, (size_t)n * ld);
+    if (!s) launch_transpose_to<float>(st, n, ld, U, M);
     ctx->dense_M = M;
   } else {
     double* M = nullptr;
-    s = dalloc(ctx, &M, nn);
-    if (!s) launch_transpose_to<double>(st, n, U, M);
+    s = dalloc(ctx, &M, (size_t)n * ld);
+    if (!s) launch_transpose_to<double>(st, n, ld, U, M);
     ctx->dense_M = M;
   }
+  ctx->dense_ld = ld;
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   dfree(ctx, G);
