@@ -438,3 +438,41 @@ def solve_uncondensed(lv, k, nu, beta, f_qp):
         pc = sol[oP + K * nP:oP + (K + 1) * nP]
         per_cell.append((e, a, pc))
     return cn, ct, per_cell
+
+
+def postprocess(e, lam, f_q, X=None):
+    """Local post-processing (stPost) of one cell: u* in [P^{k+1}(K)]^2 with
+    (grad u*_i, grad v)_K = (Lift_i., grad v)_K for all v in P^{k+1}(K) and
+    (u*, w)_K = (u_h, w)_K for constant w; Lift(u, uhat) = -L_h / nu is the
+    scheme's gradient approximation (the displayed right-hand side (L_h,
+    grad v) drops the factor -1/nu of the mixed form nu^-1 L + grad u = 0).
+    e: an Element (or OseenElement); returns u* at X (default: the data
+    points) [np, 2]."""
+    z, _ = e.recover_z(lam, f_q)
+    k = e.k
+    Minv = np.linalg.inv(e.M)
+    coef = np.array([[Minv @ (e.R[i, j] @ z) for j in range(2)] for i in range(2)])   # [i, j, nP]
+    Q = Monomials(k + 1, e.P.xc, e.P.h)
+    lv, K = e.lv, e.K
+    vs = np.sort(lv.cells[K])
+    Xq, w = quad.data_points(lv.coords[vs], k + 3)   # exact to degree 2k+5
+    w = w * e.area
+    qv, qg = Q.eval(Xq)                              # [q, r], [q, r, j]
+    psi, _ = e.P.eval(Xq)                            # P^k monomials of the lifting
+    lift = np.einsum("ijr,qr->qij", coef, psi)
+    uh = np.einsum("pai,a->pi", e.rt.eval(Xq)[0], z[:e.na])
+    A = np.einsum("q,qrj,qsj->rs", w, qg, qg)
+    mvec = w @ qv
+    n = Q.n
+    KKT = np.zeros((n + 1, n + 1))
+    KKT[:n, :n] = A
+    KKT[:n, n] = mvec
+    KKT[n, :n] = mvec
+    ustar_c = np.zeros((n, 2))
+    for i in range(2):
+        rhs = np.zeros(n + 1)
+        rhs[:n] = np.einsum("q,qj,qrj->r", w, lift[:, i, :], qg)
+        rhs[n] = w @ uh[:, i]
+        ustar_c[:, i] = np.linalg.solve(KKT, rhs)[:n]
+    X = e.xq if X is None else X
+    return Q.eval(X)[0] @ ustar_c

@@ -346,3 +346,69 @@ def test_method_reaches_direct_solution(k):
     lam, p0 = S.prob.solve_direct(f)
     assert np.linalg.norm(out["lam"] - lam) < 1e-10 * np.linalg.norm(lam)
     assert np.abs(out["p0"] - p0).max() < 1e-10 * np.abs(p0).max()
+
+
+# ------------------------------------------------------ post-processing u*
+def _errors_post(n, k, nu, beta):
+    c, t = synth.kuhn_square(n)
+    lv = mesh.Level(c, t)
+    pr = hdg.Problem(lv, k, nu, beta, 1.0)
+    f = np.array([mf.source(e.xq, nu, beta) for e in pr.elems])
+    lam, p0 = pr.solve_direct(f)
+    eu = es = 0.0
+    for K, e in enumerate(pr.elems):
+        vs = np.sort(lv.cells[K])
+        X, w = quad.data_points(lv.coords[vs], k + 4)
+        w = w * lv.area[K]
+        lk = pr.local(lam, K)
+        u, _, _, _ = e.recover(lk, p0[K], f[K], X)
+        us = hdg.postprocess(e, lk, f[K], X)
+        ue = mf.velocity(X)
+        eu += np.sum(w * np.sum((u - ue) ** 2, axis=1))
+        es += np.sum(w * np.sum((us - ue) ** 2, axis=1))
+    return np.sqrt(eu), np.sqrt(es)
+
+
+@pytest.mark.parametrize("k", [1, 2])
+@pytest.mark.parametrize("beta", [0.0, 1.0])
+def test_postprocessed_velocity_superconverges(k, beta):
+    """(stPost): u* converges at order k+2 (k >= 1), one order above u_h,
+    and is more accurate than u_h on every mesh."""
+    e = [_errors_post(n, k, 1.0, beta) for n in (4, 8, 16)]
+    rates_u = [np.log2(e[i][0] / e[i + 1][0]) for i in range(2)]
+    rates_s = [np.log2(e[i][1] / e[i + 1][1]) for i in range(2)]
+    assert rates_s[-1] > k + 2 - 0.3, (rates_s, rates_u)
+    assert rates_u[-1] < k + 1 + 0.3
+    assert all(es < eu for eu, es in e)
+
+
+def test_postprocessing_keeps_the_mean_and_matches_the_lifting():
+    k = 2
+    c, t = synth.kuhn_square(2)
+    lv = mesh.Level(c, t)
+    pr = hdg.Problem(lv, k, 0.7, 1.0, 1e2)
+    f = synth.source_uniform(3, 1, lv.n_cells, (k + 2) ** 2)[0]
+    lam, p0 = pr.solve_direct(f)
+    for K in (0, 3):
+        e = pr.elems[K]
+        lk = pr.local(lam, K)
+        vs = np.sort(lv.cells[K])
+        X, w = quad.data_points(lv.coords[vs], k + 4)
+        w = w * lv.area[K]
+        u, _, L, _ = e.recover(lk, p0[K], f[K], X)
+        us = hdg.postprocess(e, lk, f[K], X)
+        assert np.abs(w @ us - w @ u).max() < 1e-13
+        # (grad u*_i, grad v) = (-L_i./nu, grad v) for every v in P^{k+1},
+        # grad u* by central differences of the returned values (exact up
+        # to rounding for a polynomial of degree k+1 <= 3)
+        Q = hdg.Monomials(k + 1, e.P.xc, e.P.h)
+        _, qg = Q.eval(X)
+        h = 1e-5
+        gu = np.zeros(X.shape[:1] + (2, 2))
+        for d in range(2):
+            dX = np.zeros(2)
+            dX[d] = h
+            gu[:, :, d] = (hdg.postprocess(e, lk, f[K], X + dX) - hdg.postprocess(e, lk, f[K], X - dX)) / (2 * h)
+        lhs = np.einsum("q,qij,qrj->ir", w, gu, qg)
+        rhs = np.einsum("q,qij,qrj->ir", w, -L / 0.7, qg)
+        assert np.abs(lhs - rhs).max() <= 1e-6 * np.abs(rhs).max()
