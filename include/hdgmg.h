@@ -262,6 +262,19 @@ hdgmg_status hdgmg_solve_x0(hdgmg_ctx* ctx, const double* f_qp, const double* x0
                             const double* p_init, double* u_qp, double* p_qp,
                             double* state, hdgmg_info* info);
 
+/* Local post-processing (stPost): per cell the velocity u* in [P^{k+1}(K)]^2
+ * with (grad u*_i, grad v)_K = (Lift_i., grad v)_K for every v in
+ * P^{k+1}(K), Lift = -L_h / nu the scheme's gradient approximation (the
+ * displayed right-hand side (L_h, grad v) drops the factor -1/nu of the
+ * mixed form nu^-1 L + grad u = 0), and the cell mean of u_h; for k >= 1 it
+ * converges at order k+2.
+ *   f_qp     device [n_cells][n_q][2]: the source of the solve
+ *   state    device [N_skel + n_cells]: the state written by hdgmg_solve
+ *   ustar_qp device [n_cells][n_q][2] (output): u* at the data points
+ * Tangential Dirichlet data and a wind set on the context are those of the
+ * state.  ESTATE before hdgmg_assemble or with a Newton state set. */
+hdgmg_status hdgmg_postprocess(hdgmg_ctx* ctx, const double* f_qp, const double* state, double* ustar_qp);
+
 /* Wind of the Picard-linearised convection (Sec. 4.2: the previous
  * velocity), given by its values at the data points, w_qp device
  * [n_cells][n_q][2] (for instance u_qp of a previous solve), or NULL for no

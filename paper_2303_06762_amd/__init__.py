@@ -82,7 +82,7 @@ class HdgmgError(RuntimeError):
 
 
 SYMBOLS = ["hdgmg_default_opts", "hdgmg_setup", "hdgmg_assemble", "hdgmg_solve",
-           "hdgmg_solve_adjoint", "hdgmg_solve_x0", "hdgmg_set_wind", "hdgmg_set_newton", "hdgmg_set_dirichlet",
+           "hdgmg_solve_adjoint", "hdgmg_solve_x0", "hdgmg_set_wind", "hdgmg_set_newton", "hdgmg_set_dirichlet", "hdgmg_postprocess",
            "hdgmg_rhs",
            "hdgmg_apply", "hdgmg_precondition", "hdgmg_inner_solve", "hdgmg_recover",
            "hdgmg_query", "hdgmg_export", "hdgmg_kernel_timer", "hdgmg_kernel_timer_read",
@@ -119,6 +119,8 @@ def lib():
         getattr(L, name).restype = i32
     L.hdgmg_inner_solve.argtypes = [vp, vp, vp, ctypes.POINTER(i32), ctypes.POINTER(dbl)]
     L.hdgmg_inner_solve.restype = i32
+    L.hdgmg_postprocess.argtypes = [vp, vp, vp, vp]
+    L.hdgmg_postprocess.restype = i32
     L.hdgmg_recover.argtypes = [vp, vp, vp, vp, vp]
     L.hdgmg_recover.restype = i32
     L.hdgmg_query.argtypes = [vp, i32, i32, ctypes.POINTER(i64)]
@@ -297,6 +299,12 @@ class Solver:
         """Picard wind at the data points [n_cells][n_q][2] (None: no
         convection); re-assemble afterwards."""
         self._check(lib().hdgmg_set_wind(self._h, ctypes.c_void_p(None) if w_qp is None else _ptr(w_qp)))
+
+    def postprocess(self, f_qp, state):
+        """u* (stPost) at the data points [n_cells][n_q][2] of a solved state."""
+        out = self.torch.empty((self.n_cells, self.n_q, 2), dtype=self.torch.float64, device="cuda")
+        self._check(lib().hdgmg_postprocess(self._h, _ptr(f_qp), _ptr(state), _ptr(out)))
+        return out
 
     def set_newton(self, state_prev):
         """Newton linearisation at the previous state (its skeleton vector,

@@ -239,13 +239,17 @@ HDI long element_ws_size(int k) {
   return n;
 }
 
-enum { EL_CONDENSE = 0, EL_LOAD = 1, EL_RECOVER = 2, EL_GRADNU = 3 };
+enum { EL_CONDENSE = 0, EL_LOAD = 1, EL_RECOVER = 2, EL_GRADNU = 3, EL_POSTPROCESS = 4 };
 
 // The local solve of one cell.  Returns 0 on success, 1 if the KKT matrix
 // is singular.  Inputs/outputs by mode:
 //   EL_CONDENSE: out = S^eps [nK][nK] (row-major)
 //   EL_LOAD:     f [nq][2] at the data points; out = g [nK]
 //   EL_RECOVER:  f, lam [nK], p0; out = u [nq][2] then p [nq]
+//   EL_POSTPROCESS: f, lam [nK]; out = u* [nq][2] at the data points, the
+//                local post-processing (stPost): u* in [P^{k+1}]^2 with
+//                (grad u*_i, grad v) = (Lift_i., grad v) for v in P^{k+1}
+//                and the cell mean of u_h (Lift = -L_h / nu)
 //   EL_GRADNU:   two local states, (f, lam) and (f2, lam2); out[0] =
 //                -(Lift(z), Lift(z2))_K, the derivative with respect to this
 //                cell's viscosity of the adjoint-weighted residual (the only
@@ -536,7 +540,7 @@ HDI int element_local(const QuadTables& Q, const CellGeom& g, double nu, double 
   } else {
     for (int cc = 0; cc < ncol; ++cc)
       for (int a = 0; a < na; ++a) Bx[(long)a * ncol + cc] = F[cc * na + a];
-    if (mode == EL_RECOVER || mode == EL_GRADNU) {
+    if (mode == EL_RECOVER || mode == EL_GRADNU || mode == EL_POSTPROCESS) {
       for (int cc = 0; cc < ncol; ++cc) {
         const double* lm = cc == 0 ? lam : lam2;
         const bool tr = tcol && cc == 1;  // H^T: coupling H[t][a] in place of H[a][t]
@@ -636,6 +640,114 @@ HDI int element_local(const QuadTables& Q, const CellGeom& g, double nu, double 
         for (int i2 = 0; i2 < 3; ++i2)
           out[(i1 * 2 * m) * nK + i2 * 2 * m] +=
               eps_inv / g.area * (g.sigma[i1] * g.len[i1]) * (g.sigma[i2] * g.len[i2]);
+    }
+  } else if (mode == EL_POSTPROCESS) {
+    // lifting coefficients c_ij = M^-1 R_ij z (L_M, the Cholesky factor of
+    // the P^k mass, held in M), kept in Y as [ij][nP]
+    for (int ij = 0; ij < 4; ++ij) {
+      for (int r = 0; r < nP; ++r) {
+        const long row = ((long)ij * nP + r) * nz;
+        double v = 0.0;
+        for (int a = 0; a < na; ++a) v += R[row + a] * Bx[(long)a * ncol];
+        for (int i = 0; i < 3; ++i)
+          for (int j = 0; j < m; ++j) v += R[row + na + i * m + j] * lam[(i * 2 + 1) * m + j];
+        for (int p = 0; p < r; ++p) v -= M[r * nP + p] * Y[(long)ij * nP + p];
+        Y[(long)ij * nP + r] = v / M[r * nP + r];
+      }
+      for (int r = nP - 1; r >= 0; --r) {
+        double v = Y[(long)ij * nP + r];
+        for (int p = r + 1; p < nP; ++p) v -= M[p * nP + r] * Y[(long)ij * nP + p];
+        Y[(long)ij * nP + r] = v / M[r * nP + r];
+      }
+    }
+    // P^{k+1} Neumann problem with the mean constraint, two right-hand
+    // sides, in the (no longer needed) KKT storage: A [(nQ+1)^2], rhs
+    // [2][nQ+1]
+    const int nQ = (Q.k + 2) * (Q.k + 3) / 2, nA = nQ + 1;
+    WS A{Kk.p, Kk.s};
+    WS rhs{Kk.p + (long)nA * nA * Kk.s, Kk.s};
+    for (int i = 0; i < nA * nA; ++i) A[i] = 0.0;
+    for (int i = 0; i < 2 * nA; ++i) rhs[i] = 0.0;
+    double qv[28], q1[28], q2[28];
+    for (int q = 0; q < Q.nq; ++q) {
+      const double x1 = Q.xi[q][0], x2 = Q.xi[q][1];
+      const double xp[2] = {g.Xs0[0] + g.J[0][0] * x1 + g.J[0][1] * x2,
+                            g.Xs0[1] + g.J[1][0] * x1 + g.J[1][1] * x2};
+      const double wt = Q.wq[q] * g.area;
+      rt_basis(D, g, x1, x2, xp, u, gr, mono);
+      monomials(Q.k + 1, x1, x2, qv, q1, q2);
+      double lift[4] = {0.0, 0.0, 0.0, 0.0}, uh[2] = {0.0, 0.0};
+      for (int ij = 0; ij < 4; ++ij)
+        for (int r = 0; r < nP; ++r) lift[ij] += Y[(long)ij * nP + r] * mono[r];
+      for (int a = 0; a < na; ++a) {
+        uh[0] += Bx[(long)a * ncol] * u[2 * a];
+        uh[1] += Bx[(long)a * ncol] * u[2 * a + 1];
+      }
+      for (int r = 0; r < nQ; ++r) {
+        // physical gradient of the reference monomial (xi = Ji (x - X0))
+        const double gxr = q1[r] * g.Ji[0][0] + q2[r] * g.Ji[1][0];
+        const double gyr = q1[r] * g.Ji[0][1] + q2[r] * g.Ji[1][1];
+        for (int s2 = 0; s2 <= r; ++s2) {
+          const double gxs = q1[s2] * g.Ji[0][0] + q2[s2] * g.Ji[1][0];
+          const double gys = q1[s2] * g.Ji[0][1] + q2[s2] * g.Ji[1][1];
+          A[(long)r * nA + s2] += wt * (gxr * gxs + gyr * gys);
+        }
+        A[(long)r * nA + nQ] += wt * qv[r];
+        for (int i = 0; i < 2; ++i) rhs[(long)i * nA + r] += wt * (lift[2 * i] * gxr + lift[2 * i + 1] * gyr);
+      }
+      rhs[nQ] += wt * uh[0];
+      rhs[(long)nA + nQ] += wt * uh[1];
+    }
+    for (int r = 0; r < nQ; ++r) {
+      for (int s2 = 0; s2 < r; ++s2) A[(long)s2 * nA + r] = A[(long)r * nA + s2];
+      A[(long)nQ * nA + r] = A[(long)r * nA + nQ];
+    }
+    A[(long)nQ * nA + nQ] = 0.0;
+    // Gaussian elimination with partial pivoting on both right-hand sides
+    for (int j = 0; j < nA; ++j) {
+      int pr = j;
+      double best = fabs(A[(long)j * nA + j]);
+      for (int i = j + 1; i < nA; ++i)
+        if (fabs(A[(long)i * nA + j]) > best) {
+          best = fabs(A[(long)i * nA + j]);
+          pr = i;
+        }
+      if (!(best > 0)) return 1;
+      if (pr != j) {
+        for (int c = 0; c < nA; ++c) {
+          const double t = A[(long)j * nA + c];
+          A[(long)j * nA + c] = A[(long)pr * nA + c];
+          A[(long)pr * nA + c] = t;
+        }
+        for (int i = 0; i < 2; ++i) {
+          const double t = rhs[(long)i * nA + j];
+          rhs[(long)i * nA + j] = rhs[(long)i * nA + pr];
+          rhs[(long)i * nA + pr] = t;
+        }
+      }
+      const double dj = A[(long)j * nA + j];
+      for (int r = j + 1; r < nA; ++r) {
+        const double l = A[(long)r * nA + j] / dj;
+        if (l == 0.0) continue;
+        for (int c = j + 1; c < nA; ++c) A[(long)r * nA + c] -= l * A[(long)j * nA + c];
+        for (int i = 0; i < 2; ++i) rhs[(long)i * nA + r] -= l * rhs[(long)i * nA + j];
+      }
+    }
+    for (int i = 0; i < 2; ++i)
+      for (int r = nA - 1; r >= 0; --r) {
+        double v = rhs[(long)i * nA + r];
+        for (int c = r + 1; c < nA; ++c) v -= A[(long)r * nA + c] * rhs[(long)i * nA + c];
+        rhs[(long)i * nA + r] = v / A[(long)r * nA + r];
+      }
+    for (int q = 0; q < Q.nq; ++q) {
+      monomials(Q.k + 1, Q.xi[q][0], Q.xi[q][1], qv, q1, q2);
+      double us0 = 0.0, us1 = 0.0;
+      for (int r = 0; r < nQ; ++r) {
+        us0 += rhs[r] * qv[r];
+        us1 += rhs[(long)nA + r] * qv[r];
+      }
+      out[2 * q] = us0;
+      out[2 * q + 1] = us1;
     }
   } else if (mode == EL_GRADNU) {
     // -(Lift z, Lift z2)_K = -sum_ij (L_M^-1 R_ij z) . (L_M^-1 R_ij z2), with

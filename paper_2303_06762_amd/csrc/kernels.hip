@@ -105,6 +105,32 @@ __global__ void k_recover(ElemLevel E, int c0, int nbatch, const double* __restr
   }
 }
 
+// u* (stPost) at the data points of every cell of the batch: the local
+// solve from the skeleton data (and the prescribed boundary values), then
+// the P^{k+1} post-processing; out [nc][nq][2].
+__global__ void k_postprocess(ElemLevel E, int c0, int nbatch, const double* __restrict__ f,
+                              const double* __restrict__ lam, double* ws, double* ustar, int* status) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nbatch) return;
+  int c = c0 + t;
+  const int m = E.m;
+  CellGeom g;
+  cell_geom(E.X, E.cells + 3 * c, g);
+  double lk[6 * (KMAX + 1)];
+  boundary_local(E, c, lk);
+  for (int i = 0; i < 3; ++i) {
+    int d = E.cell_dofs[3 * c + i];
+    if (d < 0) continue;
+    for (int cc = 0; cc < 2; ++cc)
+      for (int j = 0; j < m; ++j) lk[(i * 2 + cc) * m + j] = lam[((long)d * 2 + cc) * m + j];
+  }
+  double nuc = E.nu_per_cell ? E.nu[c] : E.nu[0];
+  int rc = element_local(E.Q, g, nuc, E.beta, 0.0, EL_POSTPROCESS, f + (long)c * E.Q.nq * 2, lk, 0.0,
+                         WS{ws + t, nbatch}, ustar + (long)c * E.Q.nq * 2, nullptr, nullptr, E.CT,
+                         E.wcoef ? E.wcoef + (long)c * E.na : nullptr, nullptr, E.transpose != 0);
+  if (rc) atomicOr(status, 1);
+}
+
 __global__ void k_wind_fit(QuadTables Q, const double* __restrict__ X, const int* __restrict__ cells, int c0,
                            int nbatch, const double* __restrict__ vals, double* ws, double* coef, int* status) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -841,6 +867,11 @@ void launch_facet_flux(hipStream_t st, const QuadTables& Q, const double* X, con
 void launch_bd_local(hipStream_t st, int nc, int m, const int* cbf, const double* uhat_b, double* bdl) {
   const long n = (long)nc * 3 * m;
   if (n > 0) hipLaunchKernelGGL(k_bd_local, dim3(nblk(n)), dim3(TPB), 0, st, nc, m, cbf, uhat_b, bdl);
+}
+void launch_postprocess(hipStream_t st, const ElemLevel& E, int c0, int nbatch, const double* f, const double* lam,
+                        double* ws, double* ustar, int* status) {
+  hipLaunchKernelGGL(k_postprocess, dim3(nblk(nbatch, 64)), dim3(64), 0, st, E, c0, nbatch, f, lam, ws, ustar,
+                     status);
 }
 void launch_gradnu(hipStream_t st, const ElemLevel& E, int c0, int nbatch, const double* f, const double* lam,
                    const double* fa, const double* lama, double* ws, double* gnu, int* status) {

@@ -80,6 +80,10 @@ void launch_facet_flux(hipStream_t st, const QuadTables& Q, const double* X, con
 void launch_bd_local(hipStream_t st, int nc, int m, const int* cbf, const double* uhat_b, double* bdl);
 // gnu[c] += -(Lift z, Lift z_adj)_K for cells c0 .. c0+nbatch (forward
 // source f and skeleton vector lam, adjoint source fa and skeleton vector lama).
+// u* (stPost) of every cell in [c0, c0 + nbatch) at the data points:
+// ustar [nc][nq][2] (workspace: element_ws_size per cell of the batch)
+void launch_postprocess(hipStream_t st, const ElemLevel& E, int c0, int nbatch, const double* f, const double* lam,
+                        double* ws, double* ustar, int* status);
 void launch_gradnu(hipStream_t st, const ElemLevel& E, int c0, int nbatch, const double* f, const double* lam,
                    const double* fa, const double* lama, double* ws, double* gnu, int* status);
 // out = in * (w_q |K|), or in / (w_q |K|) when inverse != 0, on [nc][nq][2].

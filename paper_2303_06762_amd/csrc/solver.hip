@@ -1462,6 +1462,8 @@ hdgmg_status batched(hdgmg_ctx* ctx, DevLevel& D, const ElemLevel& E, int mode, 
       launch_load(ctx->st, E, (int)c0, nb, f, ctx->ws, out1, ctx->status);
     else if (mode == EL_GRADNU)
       launch_gradnu(ctx->st, E, (int)c0, nb, f, lam, f2, lam2, ctx->ws, out1, ctx->status);
+    else if (mode == EL_POSTPROCESS)
+      launch_postprocess(ctx->st, E, (int)c0, nb, f, lam, ctx->ws, out1, ctx->status);
     else
       launch_recover(ctx->st, E, (int)c0, nb, f, lam, p0, ctx->ws, out1, out2, ctx->status);
     HIPC(hipGetLastError());
@@ -1469,6 +1471,7 @@ hdgmg_status batched(hdgmg_ctx* ctx, DevLevel& D, const ElemLevel& E, int mode, 
   return check_status(ctx, mode == EL_CONDENSE ? "condensation"
                            : mode == EL_LOAD   ? "load"
                            : mode == EL_GRADNU ? "viscosity gradient"
+                           : mode == EL_POSTPROCESS ? "post-processing"
                                                : "recovery");
 }
 
@@ -1980,6 +1983,22 @@ hdgmg_status hdgmg_recover(hdgmg_ctx* ctx, const double* f_qp, const double* sta
   }
   TRY(batched(ctx, ctx->K, elem_level(ctx, ctx->K, true, true), EL_RECOVER, f_qp, state, state + ctx->K.ndof, u_qp,
               p_qp));
+  HIPC(hipStreamSynchronize(ctx->st));
+  return HDGMG_OK;
+}
+
+hdgmg_status hdgmg_postprocess(hdgmg_ctx* ctx, const double* f_qp, const double* state, double* ustar_qp) {
+  if (!ctx || !f_qp || !state || !ustar_qp) return HDGMG_EINVAL;
+  if (!ctx->assembled) {
+    ctx->err = "hdgmg_postprocess before hdgmg_assemble";
+    return HDGMG_ESTATE;
+  }
+  if (ctx->has_newton) {
+    ctx->err = "hdgmg_postprocess of a Newton step is not provided (its local load is kept apart)";
+    return HDGMG_ESTATE;
+  }
+  TRY(batched(ctx, ctx->K, elem_level(ctx, ctx->K, true, true), EL_POSTPROCESS, f_qp, state, nullptr, ustar_qp,
+              nullptr));
   HIPC(hipStreamSynchronize(ctx->st));
   return HDGMG_OK;
 }
