@@ -256,6 +256,56 @@ def copy_bandwidth(torch, reps=5):
     return gbs
 
 
+def sweep(hd, synth, torch, np, c, t, a):
+    """Config sweeps (one JSON line per case, printed as it finishes).
+    Stokes: 256x256 (7 levels), k in 1..4, beta in {0, 1, 1e3}, nu = 1,
+    gamma in {1, 1e2, 1e4}, FP64 and FP32-storage V-cycles; source seeded
+    uniform[-1,1) plus the gradient of the trig polynomial; inner solve #1
+    to rel. res. 1e-8 (atol 0), best of two after one warm-up.  Cavity:
+    128x128, k = 3, Re in {1, 10, 100, 1000}, a Stokes solve + 10 Picard
+    steps (oseen_workload)."""
+    rows = []
+    for k in (1, 2, 3, 4):
+        for beta in (0.0, 1.0, 1e3):
+            for gamma in (1.0, 1e2, 1e4):
+                for prec in (0, 1):
+                    t0 = time.perf_counter()
+                    s = hd.Solver(c, t, a.n_refine, k, beta, 1.0, gamma, atol=0.0, vcycle_precision=prec)
+                    s.assemble()
+                    torch.cuda.synchronize()
+                    t_asm = time.perf_counter() - t0
+                    X = s.data_points().cpu().numpy()
+                    f = synth.source_uniform(0, 1, s.n_cells, s.n_q)[0] + synth.trig_gradient(X, 1)
+                    g = s.rhs(torch.as_tensor(f, device="cuda"))
+                    x = torch.empty_like(g)
+                    s.inner_solve(g, x)
+                    best = None
+                    for _ in range(2):
+                        torch.cuda.synchronize()
+                        t0 = time.perf_counter()
+                        _, its, rel, st = s.inner_solve(g, x)
+                        torch.cuda.synchronize()
+                        dt = time.perf_counter() - t0
+                        best = dt if best is None else min(best, dt)
+                    row = {"case": "stokes 256x256", "k": k, "beta": beta, "gamma": gamma,
+                           "vcycle": "fp64" if prec == 0 else "fp32", "n_skel": s.n_skel, "iterations": its,
+                           "status": st, "rel_res": rel, "ms": 1e3 * best, "dofs_per_s": s.n_skel / best,
+                           "setup_assemble_s": t_asm}
+                    print(json.dumps(row), flush=True)
+                    rows.append(row)
+                    s.close()
+    for re_ in (1.0, 10.0, 100.0, 1000.0):
+        o = oseen_workload(hd, synth, torch, np, 10, re_)
+        its = [i for step in o["fgmres_its_per_uzawa_step"] for i in step]
+        row = {"case": "cavity 128x128 k=3", "Re": re_, "value": o["value"], "solve_s": o["solve_s"],
+               "assemble_s_total": o["assemble_s_total"], "avg_fgmres_its": float(np.mean(its)),
+               "uzawa_steps": [len(step) for step in o["fgmres_its_per_uzawa_step"]],
+               "picard_max_du": o["picard_max_du"]}
+        print(json.dumps(row), flush=True)
+        rows.append(row)
+    print(json.dumps({"sweep_cases": len(rows)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -272,6 +322,10 @@ def main():
     ap.add_argument("--re", type=float, default=100.0)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the batch-gradient workload")
     ap.add_argument("--adjoint-rhs", type=int, default=16)
+    ap.add_argument("--sweep", action="store_true",
+                    help="parameter sweeps instead of the bench line: the 256x256 generalized Stokes "
+                         "workload over k, beta, gamma and V-cycle precision, and the cavity over Re; "
+                         "one JSON line per case, then a summary line")
     ap.add_argument("--profile-run", action="store_true",
                     help="counter-collection run: a 1 GiB device copy (calibration of the HBM "
                          "counters) then two FP64 inner solves; prints a summary only")
@@ -287,6 +341,9 @@ def main():
 
     torch.cuda.set_device(0)
     c, t = synth.kuhn_square(4)
+    if a.sweep:
+        sweep(hd, synth, torch, np, c, t, a)
+        return
     if a.profile_run:
         # calibration: a plain copy of exactly 1 GiB read + 1 GiB written
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
