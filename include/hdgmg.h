@@ -134,12 +134,15 @@ typedef struct {
                               GEMV instead of running the kernel (the same
                               linear operator up to rounding); 0: the
                               kernel runs in every V-cycle              */
+  int rec_wide;            /* 1: every record-smoothed level uses the 32-bit
+                              record form (otherwise only levels beyond
+                              65535 interior facets); same results      */
 } hdgmg_opts;
 
 /* Defaults: m_p = m_h = 1, V-cycle, growth 2, rtol 1e-8, atol 1e-10,
  * max_it 500, uzawa_max 50, uzawa_tol 1e-10, coarse_dofs 2048,
  * stream_dofs 65536, vcycle_precision 0, oseen 0, restart 50, transpose 0,
- * coarse_dense 1. */
+ * coarse_dense 1, rec_wide 0. */
 void hdgmg_default_opts(hdgmg_opts* opts);
 
 #define HDGMG_MAX_UZAWA 64

@@ -314,8 +314,9 @@ __global__ void __launch_bounds__(CT) k_coarse_cycle(const CoarseLevel* __restri
 // with items whose row marker is REC_PAD), a thread per patch row, so that a
 // thread's item index needs no lookup.  Patches of one colour share no cell,
 // so the rows a batch reads are never written by another batch of the same
-// launch.
-template <int NS, typename TS>
+// launch.  W (wide records, levels beyond 16-bit facet indices): two meta
+// words per item, (unknown, row in patch, F0, F1) and (F2, F3, F4, 0).
+template <int NS, typename TS, bool W>
 __global__ void __launch_bounds__(GS_REC_THREADS)
     k_gs_records(const uint4* __restrict__ meta, const TS* __restrict__ val, const TS* __restrict__ ainv, int nit,
                  int nsm, int b0, double* __restrict__ u, const double* __restrict__ g) {
@@ -329,7 +330,8 @@ __global__ void __launch_bounds__(GS_REC_THREADS)
   // every load of the item is independent of the others: issue them
   // together, the meta word first (the gathers wait only for it).  The two
   // orders below are the faster schedules measured for each precision.
-  const uint4 m0 = meta[t];
+  const uint4 m0 = meta[W ? 2 * (long)t : t];
+  const uint4 m1 = W ? meta[2 * (long)t + 1] : m0;
   V vv[(COARSE_NNZ + G - 1) / G];
   V av[NS / G];
   if constexpr (G == 4) {
@@ -348,14 +350,16 @@ __global__ void __launch_bounds__(GS_REC_THREADS)
   for (int e = 0; e < (COARSE_NNZ + G - 1) / G; ++e)
 #pragma unroll
     for (int i = 0; i < G; ++i) vals[e * G + i] = GT::get(vv[e], i);
-  const unsigned k = m0.x;
-  const bool on = (k >> REC_LOC_SHIFT) != REC_PAD;
+  const unsigned dof = W ? m0.x : (m0.x & REC_DOF_MASK);
+  const unsigned loc = W ? m0.y : (m0.x >> REC_LOC_SHIFT);
+  const bool on = loc != REC_PAD;
   const unsigned fw[3] = {m0.y, m0.z, m0.w};
-  double r = g[k & REC_DOF_MASK];
+  const unsigned fwide[5] = {m0.z, m0.w, m1.x, m1.y, m1.z};
+  double r = g[dof];
 #pragma unroll
   for (int q = 0; q < COARSE_NNZ / 2; ++q) {
-    const int F = (fw[q / 2] >> (16 * (q % 2))) & 0xffff;
-    const double2 uf = *(const double2*)(u + 2 * F);
+    const unsigned F = W ? fwide[q] : (fw[q / 2] >> (16 * (q % 2))) & 0xffff;
+    const double2 uf = *(const double2*)(u + 2 * (long)F);
     r -= (double)vals[2 * q] * uf.x + (double)vals[2 * q + 1] * uf.y;
   }
   res[tid] = on ? r : 0.0;
@@ -367,41 +371,49 @@ __global__ void __launch_bounds__(GS_REC_THREADS)
     for (int j = 0; j < NS / G; ++j) asm volatile("" ::"v"(av[j]));
   __syncthreads();
   if (on) {
-    const int base = tid - (int)(k >> REC_LOC_SHIFT);
+    const int base = tid - (int)loc;
     double d = 0.0;
 #pragma unroll
     for (int j = 0; j < NS / G; ++j)
       if (G == 2 || j * G < nsm)  // FP64 rows past nsm are zero; FP32 ones are not loaded
 #pragma unroll
         for (int i = 0; i < G; ++i) d += (double)GT::get(av[j], i) * res[base + j * G + i];
-    u[k & REC_DOF_MASK] += d;
+    u[dof] += d;
   }
 }
 
+template <typename TS, bool W>
+void gs_records_tw(hipStream_t st, const uint4* meta, const TS* val, const TS* ainv, int nit, int nsm, int b0,
+                   int nb, double* u, const double* g) {
+  if (nsm <= 12)
+    hipLaunchKernelGGL((k_gs_records<12, TS, W>), dim3(nb), dim3(GS_REC_THREADS), 0, st, meta, val, ainv, nit, nsm,
+                       b0, u, g);
+  else if (nsm <= 16)
+    hipLaunchKernelGGL((k_gs_records<16, TS, W>), dim3(nb), dim3(GS_REC_THREADS), 0, st, meta, val, ainv, nit, nsm,
+                       b0, u, g);
+  else
+    hipLaunchKernelGGL((k_gs_records<32, TS, W>), dim3(nb), dim3(GS_REC_THREADS), 0, st, meta, val, ainv, nit, nsm,
+                       b0, u, g);
+}
 template <typename TS>
 void gs_records_t(hipStream_t st, const uint4* meta, const TS* val, const TS* ainv, int nit, int nsm, int b0,
-                  int nb, double* u, const double* g) {
-  if (nsm <= 12)
-    hipLaunchKernelGGL((k_gs_records<12, TS>), dim3(nb), dim3(GS_REC_THREADS), 0, st, meta, val, ainv, nit, nsm, b0,
-                       u, g);
-  else if (nsm <= 16)
-    hipLaunchKernelGGL((k_gs_records<16, TS>), dim3(nb), dim3(GS_REC_THREADS), 0, st, meta, val, ainv, nit, nsm, b0,
-                       u, g);
+                  int nb, double* u, const double* g, bool wide) {
+  if (wide)
+    gs_records_tw<TS, true>(st, meta, val, ainv, nit, nsm, b0, nb, u, g);
   else
-    hipLaunchKernelGGL((k_gs_records<32, TS>), dim3(nb), dim3(GS_REC_THREADS), 0, st, meta, val, ainv, nit, nsm, b0,
-                       u, g);
+    gs_records_tw<TS, false>(st, meta, val, ainv, nit, nsm, b0, nb, u, g);
 }
 
 }  // namespace
 
 void launch_gs_records(hipStream_t st, const unsigned* meta, const void* val, const void* ainv, int nit, int nsm,
-                       int b0, int nb, double* u, const double* g, int f32) {
+                       int b0, int nb, double* u, const double* g, int f32, int wide) {
   if (nb <= 0) return;
   const uint4* m = (const uint4*)meta;
   if (f32)
-    gs_records_t<float>(st, m, (const float*)val, (const float*)ainv, nit, nsm, b0, nb, u, g);
+    gs_records_t<float>(st, m, (const float*)val, (const float*)ainv, nit, nsm, b0, nb, u, g, wide != 0);
   else
-    gs_records_t<double>(st, m, (const double*)val, (const double*)ainv, nit, nsm, b0, nb, u, g);
+    gs_records_t<double>(st, m, (const double*)val, (const double*)ainv, nit, nsm, b0, nb, u, g, wide != 0);
 }
 
 template <typename TS, bool GT>

@@ -63,9 +63,11 @@ constexpr int GS_REC_THREADS = 256;
 // CoarseLevel: meta, val, ainv over nit items), batches [b0, b0 + nb) of
 // exactly GS_REC_THREADS item slots each (patch-aligned, padded with items
 // whose row marker is REC_PAD): u += A_ss^-1 (g - A u)_s for every patch of
-// the colour.  f32: val and ainv are float, else double.
+// the colour.  f32: val and ainv are float, else double.  wide: two meta
+// words per item, (unknown, row in patch, F0, F1), (F2, F3, F4, 0) with
+// 32-bit fields, for levels beyond 16-bit facet indices.
 void launch_gs_records(hipStream_t st, const unsigned* meta, const void* val, const void* ainv, int nit, int nsm,
-                       int b0, int nb, double* u, const double* g, int f32);
+                       int b0, int nb, double* u, const double* g, int f32, int wide);
 
 // u_top <- MG_h(top, g_top, u_top, m_top, q) with m(l-1) = growth m(l) on
 // levels 0..top (top <= the levels described by Ls); level 0 is solved with

@@ -601,6 +601,42 @@ __global__ void k_ell_spmv(int n, int w, const int* __restrict__ ci, const TS* _
   y[r] = beta_y == 0.0 ? s : beta_y * y[r] + s;
 }
 
+// The same product with a group of L lanes per row (L a power of two, at
+// most 8): lane j of the group takes the slots j, j + L, ..., eight of them
+// in flight at once, and the group sums by shuffles -- wide rows (the
+// restrictions carry the harmonic-extension correction) cost one or two
+// memory round trips instead of one per eight slots.
+template <typename TS, int L>
+__global__ void k_ell_spmv_g(int n, int w, const int* __restrict__ ci, const TS* __restrict__ v,
+                             const double* __restrict__ x, double* y, double beta_y, double* zero_out) {
+  const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long r = tid / L;
+  const int j = (int)(tid % L);
+  const bool ok = r < n;  // every lane stays for the shuffles
+  double s = 0.0;
+  if (ok) {
+    for (int k0 = j; k0 < w; k0 += 8 * L) {
+      TS vv[8];
+      int cc[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int k = k0 + q * L;
+        const long kk = min(k, w - 1);
+        vv[q] = v[kk * n + r] * (TS)(k < w);
+        cc[q] = ci[kk * n + r];
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) s += (double)vv[q] * x[cc[q]];
+    }
+  }
+#pragma unroll
+  for (int off = L / 2; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if (ok && j == 0) {
+    if (zero_out) zero_out[r] = 0.0;
+    y[r] = beta_y == 0.0 ? s : beta_y * y[r] + s;
+  }
+}
+
 template <typename TS>
 __global__ void k_gemv_dense(int n, const TS* __restrict__ A, const double* __restrict__ x,
                              double* __restrict__ y) {
@@ -936,7 +972,20 @@ template <typename TS>
 void launch_ell_spmv(hipStream_t st, int n, int w, const int* ci, const TS* v, const double* x, double* y,
                      double beta_y, double* zero_out) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_ell_spmv<TS>, dim3(nblk(n)), dim3(TPB), 0, st, n, w, ci, v, x, y, beta_y, zero_out);
+  if (w <= 8) {
+    hipLaunchKernelGGL(k_ell_spmv<TS>, dim3(nblk(n)), dim3(TPB), 0, st, n, w, ci, v, x, y, beta_y, zero_out);
+    return;
+  }
+  const long nt2 = 2L * n, nt4 = 4L * n, nt8 = 8L * n;
+  if (w <= 16)
+    hipLaunchKernelGGL((k_ell_spmv_g<TS, 2>), dim3(nblk(nt2)), dim3(TPB), 0, st, n, w, ci, v, x, y, beta_y,
+                       zero_out);
+  else if (w <= 32)
+    hipLaunchKernelGGL((k_ell_spmv_g<TS, 4>), dim3(nblk(nt4)), dim3(TPB), 0, st, n, w, ci, v, x, y, beta_y,
+                       zero_out);
+  else
+    hipLaunchKernelGGL((k_ell_spmv_g<TS, 8>), dim3(nblk(nt8)), dim3(TPB), 0, st, n, w, ci, v, x, y, beta_y,
+                       zero_out);
 }
 template void launch_ell_spmv<double>(hipStream_t, int, int, const int*, const double*, const double*, double*,
                                       double, double*);

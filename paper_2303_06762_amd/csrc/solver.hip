@@ -54,8 +54,8 @@ struct DevLevel {
   double *u = nullptr, *g = nullptr, *r = nullptr;  // multigrid vectors
   // record-based Gauss-Seidel (launched lowest-order levels): patch-row
   // records in the V-cycle's storage, batches per colour
-  bool rec = false;
-  unsigned* rk = nullptr;  // [2][nit][4] meta words
+  bool rec = false, rwide = false;  // rwide: 32-bit record fields (8 meta words per item)
+  unsigned* rk = nullptr;  // [nit][4] meta words ([nit][8] when rwide)
   const void *rv = nullptr, *ra = nullptr;
   std::vector<int> rcb;
   int rnit = 0, rnsm = 0;
@@ -260,6 +260,9 @@ namespace {
 // (e.g. PyTorch's caching allocator), else hipMalloc / hipFree.
 // Largest level (unknowns) whose MG_h is tabulated as a dense matrix.
 constexpr int DENSE_MAX_N = 8192;
+// Launched lowest-order levels with at most this many interior facets smooth
+// with the patch-row record kernel (beyond 65535: the 32-bit record form).
+constexpr int REC_MAX_FACETS = 1 << 22;
 
 void* dmalloc(hdgmg_ctx* ctx, size_t bytes) {
   if (ctx->alloc_fn) return ctx->alloc_fn(bytes, ctx->alloc_ctx);
@@ -561,7 +564,7 @@ void sweep(hdgmg_ctx* ctx, DevLevel& D, double* x, const double* b, bool forward
     if (D.rec) {
       int t = kt_begin(ctx, 2);
       launch_gs_records(ctx->st, D.rk, D.rv, D.ra, D.rnit, D.rnsm, D.rcb[c], D.rcb[c + 1] - D.rcb[c], x, b,
-                        D.f32 ? 1 : 0);
+                        D.f32 ? 1 : 0, D.rwide ? 1 : 0);
       kt_end(ctx, 2, t, phase_bytes(ctx, D, level, c));
     } else if (D.fast) {
       // colour phase = cell apply (all cells) + patch relaxation (colour c)
@@ -997,6 +1000,7 @@ hdgmg_status build_transfers(hdgmg_ctx* ctx) {
 // max_items.  Also the padded residual rows per unknown.
 struct LevelRecords {
   int n = 0, nit = 0, nsm = 0;
+  bool wide = false;  // 32-bit fields, 8 meta words per item
   std::vector<unsigned> meta;
   std::vector<double> val, ainv;
   std::vector<int> cb, bitem, bwd;
@@ -1007,12 +1011,14 @@ struct LevelRecords {
 // pad: every batch fills exactly max_items item slots (padding items carry
 // the row marker REC_PAD and zero values), so that batch b starts at item
 // b * max_items.
-hdgmg_status level_records(hdgmg_ctx* ctx, int l, int max_items, LevelRecords& R, bool pad = false) {
+hdgmg_status level_records(hdgmg_ctx* ctx, int l, int max_items, LevelRecords& R, bool pad = false,
+                           bool wide = false) {
   const Level& L = ctx->lv[l];
   const int n = 2 * L.nint;
   R = LevelRecords();
   R.n = n;
-  if (L.nint > 65535) {
+  R.wide = wide;
+  if (!wide && (L.nint > 65535 || n > (int)REC_DOF_MASK)) {
     ctx->err = "level too large for 16-bit record facet indices";
     return HDGMG_EMESH;
   }
@@ -1107,7 +1113,8 @@ hdgmg_status level_records(hdgmg_ctx* ctx, int l, int max_items, LevelRecords& R
   }
   const int nit = (int)idof.size();
   R.nit = nit;
-  R.meta.assign((size_t)4 * nit, 0u);
+  const int MW = wide ? 8 : 4;  // meta words per item
+  R.meta.assign((size_t)MW * nit, 0u);
   // value groups: pairs for FP64 storage, quads for FP32 (16-byte loads)
   const int G = vc_f32(ctx) ? 4 : 2;
   const int nvg = (COARSE_NNZ + G - 1) / G, nag = (std::max(nsm, 1) + G - 1) / G;
@@ -1115,12 +1122,21 @@ hdgmg_status level_records(hdgmg_ctx* ctx, int l, int max_items, LevelRecords& R
   R.ainv.assign((size_t)nag * G * nit, 0.0);
   for (int t = 0; t < nit; ++t) {
     if (idof[t] < 0) {  // padding: row marker REC_PAD, unknown 0, zero values
-      R.meta[(size_t)t * 4] = REC_PAD << REC_LOC_SHIFT;
+      if (wide)
+        R.meta[(size_t)t * 8 + 1] = REC_PAD;
+      else
+        R.meta[(size_t)t * 4] = REC_PAD << REC_LOC_SHIFT;
       continue;
     }
     // meta (key, F0 | F1 << 16, F2 | F3 << 16, F4): the row's columns come in
-    // facet pairs (2F, 2F + 1), sorted, padded with zero entries
-    R.meta[(size_t)t * 4] = (unsigned)idof[t] | ((unsigned)iloc[t] << REC_LOC_SHIFT);
+    // facet pairs (2F, 2F + 1), sorted, padded with zero entries; wide:
+    // (unknown, row, F0, F1), (F2, F3, F4, 0)
+    if (wide) {
+      R.meta[(size_t)t * 8] = (unsigned)idof[t];
+      R.meta[(size_t)t * 8 + 1] = (unsigned)iloc[t];
+    } else {
+      R.meta[(size_t)t * 4] = (unsigned)idof[t] | ((unsigned)iloc[t] << REC_LOC_SHIFT);
+    }
     // values in groups of G: entry e of item t at [((e / G) * nit + t) * G + e % G]
     // the row's entries straight from the CSR (contiguous), zero beyond its length
     const int r0 = A.rp[idof[t]], nz = A.rp[idof[t] + 1] - r0;
@@ -1135,7 +1151,10 @@ hdgmg_status level_records(hdgmg_ctx* ctx, int l, int max_items, LevelRecords& R
         ctx->err = "lowest-order row whose columns are not facet pairs";
         return HDGMG_EMESH;
       }
-      R.meta[(size_t)t * 4 + 1 + q / 2] |= (unsigned)(padded ? 0 : c0 / 2) << (16 * (q % 2));
+      if (wide)
+        R.meta[(size_t)t * 8 + 2 + q] = (unsigned)(padded ? 0 : c0 / 2);
+      else
+        R.meta[(size_t)t * 4 + 1 + q / 2] |= (unsigned)(padded ? 0 : c0 / 2) << (16 * (q % 2));
     }
     for (int j = 0; j < nsm; ++j) R.ainv[((size_t)(j / G) * nit + t) * G + j % G] = irow[(size_t)t * nsm + j];
   }
@@ -1320,11 +1339,13 @@ hdgmg_status build_record_levels(hdgmg_ctx* ctx) {
     D.rec = false;
     const Level& L = ctx->lv[l];
     // records replace the streaming pair (cell apply + patch relaxation) on
-    // levels small enough for 16-bit facet indices; stream_dofs = 0 keeps
-    // the streaming kernels on every level
-    if (L.nint > 65535 || 2 * L.max_patch_facets > 32 || (D.fast && ctx->opts.stream_dofs == 0)) continue;
+    // the launched lowest-order levels (32-bit fields beyond 16-bit facet
+    // indices); stream_dofs = 0 keeps the streaming kernels on every level
+    if (L.nint > REC_MAX_FACETS || 2 * L.max_patch_facets > 32 || (D.fast && ctx->opts.stream_dofs == 0)) continue;
+    const bool wide = ctx->opts.rec_wide || L.nint > 65535 || 2 * L.nint > (int)REC_DOF_MASK;
     LevelRecords R;
-    TRY(level_records(ctx, l, GS_REC_THREADS, R, true));
+    TRY(level_records(ctx, l, GS_REC_THREADS, R, true, wide));
+    D.rwide = wide;
     TRY(upload(ctx, &D.rk, R.meta));
     TRY(upload_vals(ctx, R.val, &D.rv));
     TRY(upload_vals(ctx, R.ainv, &D.ra));
@@ -1336,8 +1357,8 @@ hdgmg_status build_record_levels(hdgmg_ctx* ctx) {
     for (int c = 0; c < L.ncol; ++c) {
       double items = 0.0;  // patch rows, padding excluded
       for (int t = R.bitem[R.cb[c]]; t < R.bitem[R.cb[c + 1]]; ++t)
-        items += (R.meta[(size_t)t * 4] >> REC_LOC_SHIFT) != REC_PAD;
-      D.rec_bytes[c] = items * (16.0 + ws * (COARSE_NNZ + R.nsm) + 8.0 * (COARSE_NNZ + 2));
+        items += wide ? R.meta[(size_t)t * 8 + 1] != REC_PAD : (R.meta[(size_t)t * 4] >> REC_LOC_SHIFT) != REC_PAD;
+      D.rec_bytes[c] = items * ((wide ? 32.0 : 16.0) + ws * (COARSE_NNZ + R.nsm) + 8.0 * (COARSE_NNZ + 2));
     }
     D.rec = true;
   }
@@ -1537,6 +1558,7 @@ void hdgmg_default_opts(hdgmg_opts* o) {
   o->restart = 50;
   o->transpose = 0;
   o->coarse_dense = 1;
+  o->rec_wide = 0;
 }
 
 const char* hdgmg_last_error(const hdgmg_ctx* ctx) {
@@ -1601,7 +1623,7 @@ hdgmg_status hdgmg_setup(const hdgmg_mesh* mesh, int k, double beta, const doubl
       ctx->opts.vcycle_precision < 0 || ctx->opts.vcycle_precision > 2 || ctx->opts.oseen < 0 ||
       ctx->opts.oseen > 1 || ctx->opts.restart < 1 || ctx->opts.restart > 64 || ctx->opts.transpose < 0 ||
       ctx->opts.transpose > 1 || (ctx->opts.transpose && !ctx->opts.oseen) || ctx->opts.coarse_dense < 0 ||
-      ctx->opts.coarse_dense > 1) {
+      ctx->opts.coarse_dense > 1 || ctx->opts.rec_wide < 0 || ctx->opts.rec_wide > 1) {
     g_setup_error = "invalid options";
     delete ctx;
     return HDGMG_EINVAL;

@@ -36,7 +36,8 @@ _ORACLES = {}
 
 
 def oracle_setup(key, coords, cells, n_refine, k, nu, beta, gamma, **kw):
-    kw = {a: b for a, b in kw.items() if a not in ("coarse_dofs", "stream_dofs", "coarse_dense")}  # layout only
+    kw = {a: b for a, b in kw.items()
+          if a not in ("coarse_dofs", "stream_dofs", "coarse_dense", "rec_wide")}  # layout only
     if key not in _ORACLES:
         _ORACLES[key] = solver.Setup(coords, cells, n_refine, k, nu, beta, gamma, **kw)
     return _ORACLES[key]
@@ -98,6 +99,11 @@ CASES = {
     # coarse kernel smooth with the record kernel (residuals stay streamed)
     "k1_stream_rec": (lambda: synth.kuhn_square(4), 2, 1, 1.0, 1.0, 1e2, dict(stream_dofs=1, coarse_dofs=200)),
     "k2_stream_rec": (lambda: synth.kuhn_square(4), 2, 2, 0.8, 0.5, 1e2, dict(stream_dofs=1, coarse_dofs=0)),
+    # the 32-bit record form (levels beyond 65535 facets) forced on every level
+    "k2_stream_rec_wide": (lambda: synth.kuhn_square(4), 2, 2, 0.8, 0.5, 1e2,
+                           dict(stream_dofs=1, coarse_dofs=0, rec_wide=1)),
+    "k1_rec_wide_split": (lambda: synth.kuhn_square(4), 2, 1, 1.0, 1.0, 1e2,
+                          dict(stream_dofs=1, coarse_dofs=200, rec_wide=1)),
 }
 
 
