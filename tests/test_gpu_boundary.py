@@ -87,3 +87,48 @@ def test_div_l2_is_round_off(k, gamma):
     assert info["div_l2"] <= 1e-8 * unorm, (info["div_l2"], unorm)
     assert info["t_solve"] > 0.0
     s.close()
+
+
+def test_pressure_robustness_at_128x128():
+    # Pressure robustness on the GPU path at the batch-gradient size (128x128
+    # squares, 32768 cells, k = 2): adding grad(phi_h) to f, phi_h continuous
+    # and piecewise linear (on the 4x4 coarse mesh, hence on every refined
+    # mesh), leaves u_h unchanged and shifts p_h by phi_h minus its mean.
+    import paper_2303_06762_amd as hd
+    print("pressure robustness 128x128 k=2", flush=True)
+    c, t = synth.kuhn_square(4)
+    nr, k = 5, 2
+    s = hd.Solver(c, t, nr, k, 1.0, 1.0, 1e2, rtol=1e-11, atol=0.0, uzawa_tol=1e-12)
+    s.assemble()
+    X = s.data_points().cpu().numpy()                      # [n_cells][n_q][2]
+    n_cells = s.n_cells
+    modes, a, th = synth.trig_coefficients(1)
+    phi_v = np.sum(a[None, :] * np.cos(np.pi * c @ modes.T + th[None, :]), axis=1)
+    # coarse ancestor of each fine cell (children 4c + i on every level)
+    anc = np.arange(n_cells) >> (2 * nr)
+    grads = np.zeros((len(t), 2))
+    for K in range(len(t)):
+        V = c[t[K]]
+        Mb = np.array([[V[1, 0] - V[0, 0], V[2, 0] - V[0, 0]], [V[1, 1] - V[0, 1], V[2, 1] - V[0, 1]]])
+        grads[K] = np.linalg.solve(Mb.T, phi_v[t[K][1:]] - phi_v[t[K][0]])
+    V0 = c[t[anc, 0]]
+    phi_q = phi_v[t[anc, 0]][:, None] + np.einsum("cqj,cj->cq", X - V0[:, None, :], grads[anc])
+    f1 = synth.source_uniform(0, 1, n_cells, s.n_q)[0]
+    f2 = f1 + grads[anc][:, None, :]
+    u1, p1, _, i1, st1 = s.solve(dev(f1))
+    u2, p2, _, i2, st2 = s.solve(dev(f2))
+    assert st1 == 0 and st2 == 0
+    u1, u2, p1, p2 = (x.cpu().numpy() for x in (u1, u2, p1, p2))
+    W = s.data_weights().cpu().numpy()
+    unorm = np.sqrt(np.sum(W[..., None] * u1 ** 2))
+    du = np.sqrt(np.sum(W[..., None] * (u2 - u1) ** 2))
+    assert du <= 1e-8 * unorm, (du, unorm)
+    shift = phi_q - np.sum(W * phi_q) / np.sum(W)
+    assert np.abs((p2 - p1) - shift).max() <= 1e-7 * np.abs(shift).max()
+    # the same size of non-gradient forcing does move u_h (the check has power)
+    f3 = f1 + np.stack([-grads[anc][:, 1], grads[anc][:, 0]], axis=-1)[:, None, :]
+    u3, _, _, _, st3 = s.solve(dev(f3))
+    assert st3 == 0
+    du3 = np.sqrt(np.sum(W[..., None] * (u3.cpu().numpy() - u1) ** 2))
+    assert du3 >= 1e-2 * unorm, (du3, unorm)
+    s.close()
