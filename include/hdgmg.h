@@ -251,6 +251,32 @@ hdgmg_status hdgmg_solve_adjoint(hdgmg_ctx* ctx, const double* f_qp, const doubl
                                  const double* gu_qp, double* gf_qp, double* gnu,
                                  double* adj_state, hdgmg_info* info);
 
+/* A batch of nrhs right-hand sides over nctx contexts set up and assembled
+ * for the same problem (identical mesh, order, coefficients and options;
+ * sizes are checked): right-hand side i is solved by context i % nctx, each
+ * context working through its share on its own stream in a host thread of
+ * its own, so that independent solves overlap on the device.  Arrays are
+ * the single-solve layouts stacked over the batch: f_qp, u_qp
+ * [nrhs][n_cells][n_q][2], p_qp [nrhs][n_cells][n_q], states (may be NULL)
+ * [nrhs][N_skel + n_cells], infos (host, may be NULL) [nrhs].  The inputs
+ * must be complete before the call (synchronise the stream that produced
+ * them); the call returns after every context's stream has finished.
+ * Returns the first negative status, else the largest (NOT_CONVERGED if
+ * any solve did not converge); EINVAL for a context given twice. */
+hdgmg_status hdgmg_solve_batch(hdgmg_ctx* const* ctxs, int nctx, int nrhs,
+                               const double* f_qp, double* u_qp, double* p_qp,
+                               double* states, hdgmg_info* infos);
+
+/* The adjoint of a batch (hdgmg_solve_adjoint per right-hand side, spread
+ * over the contexts as hdgmg_solve_batch): f_qp, states, gu_qp and gf_qp
+ * stacked over the batch; gnu device [nctx][n_cells] or NULL, row c
+ * ACCUMULATED by context c over its share (sum the rows for dJ/dnu of the
+ * whole batch). */
+hdgmg_status hdgmg_solve_adjoint_batch(hdgmg_ctx* const* ctxs, int nctx, int nrhs,
+                                       const double* f_qp, const double* states,
+                                       const double* gu_qp, double* gf_qp,
+                                       double* gnu, hdgmg_info* infos);
+
 /* hdgmg_solve from an initial iterate: x0 (device, N_skel, may be NULL for
  * zero) starts the first inner solve of the AL-Uzawa iteration; for Picard
  * and Newton steps (Sec. 4.2) it is the previous step's skeleton vector

@@ -83,6 +83,7 @@ class HdgmgError(RuntimeError):
 
 SYMBOLS = ["hdgmg_default_opts", "hdgmg_setup", "hdgmg_assemble", "hdgmg_solve",
            "hdgmg_solve_adjoint", "hdgmg_solve_x0", "hdgmg_set_wind", "hdgmg_set_newton", "hdgmg_set_dirichlet", "hdgmg_postprocess",
+           "hdgmg_solve_batch", "hdgmg_solve_adjoint_batch",
            "hdgmg_rhs",
            "hdgmg_apply", "hdgmg_precondition", "hdgmg_inner_solve", "hdgmg_recover",
            "hdgmg_query", "hdgmg_export", "hdgmg_kernel_timer", "hdgmg_kernel_timer_read",
@@ -119,6 +120,11 @@ def lib():
         getattr(L, name).restype = i32
     L.hdgmg_inner_solve.argtypes = [vp, vp, vp, ctypes.POINTER(i32), ctypes.POINTER(dbl)]
     L.hdgmg_inner_solve.restype = i32
+    L.hdgmg_solve_batch.argtypes = [ctypes.POINTER(vp), i32, i32, vp, vp, vp, vp, ctypes.POINTER(Info)]
+    L.hdgmg_solve_batch.restype = i32
+    L.hdgmg_solve_adjoint_batch.argtypes = [ctypes.POINTER(vp), i32, i32, vp, vp, vp, vp, vp,
+                                            ctypes.POINTER(Info)]
+    L.hdgmg_solve_adjoint_batch.restype = i32
     L.hdgmg_postprocess.argtypes = [vp, vp, vp, vp]
     L.hdgmg_postprocess.restype = i32
     L.hdgmg_recover.argtypes = [vp, vp, vp, vp, vp]
@@ -382,15 +388,7 @@ def _make_function():
         @staticmethod
         def forward(ctx, solver, f_qp, nu):
             pool = list(solver) if isinstance(solver, (list, tuple)) else [solver]
-            f_qp = f_qp.contiguous()
-
-            def run(s, idx):
-                return [s.solve(f_qp[i])[:3] for i in idx]
-
-            res = _over_pool(pool, f_qp.shape[0], run)
-            us = torch.stack([r[0] for r in res])
-            states = torch.stack([r[2] for r in res])
-            torch.cuda.synchronize()
+            us, _, states, _ = solve_batch(pool, f_qp)
             ctx.pool = pool
             ctx.save_for_backward(f_qp, states)
             return us
@@ -398,56 +396,72 @@ def _make_function():
         @staticmethod
         def backward(ctx, gu):
             f_qp, states = ctx.saved_tensors
-            pool = ctx.pool
-            gu = gu.contiguous()
-            # one viscosity-gradient accumulator per solver (per stream)
-            gnus = [torch.zeros(s.n_cells, dtype=torch.float64, device=f_qp.device) for s in pool]
-
-            def run(s, idx):
-                g = gnus[pool.index(s)]
-                return [s.solve_adjoint(f_qp[i], states[i], gu[i], gnu=g)[0] for i in idx]
-
-            gfs = _over_pool(pool, f_qp.shape[0], run)
-            gf = torch.stack(gfs)
-            gnu = torch.stack(gnus).sum(dim=0)
-            torch.cuda.synchronize()
+            gf, gnu = solve_adjoint_batch(ctx.pool, f_qp, states, gu)
             return None, gf, gnu
 
     return StokesSolve
 
 
-def _over_pool(pool, n, run):
-    """Right-hand sides 0..n-1 dealt round-robin over the solvers of `pool`
-    (one context per HIP stream), each solver's share run by a host thread
-    of its own with its stream current (the library calls release the
-    interpreter lock), so that independent solves overlap on the device.
-    Returns the n results in order."""
-    import torch
-    shares = [list(range(j, n, len(pool))) for j in range(len(pool))]
-    # inputs (and zeroed accumulators) come from the caller's stream
+def _batch_handles(pool):
+    for p_ in pool:
+        if getattr(p_, "_h", None) is None or not p_._h.value:
+            raise ValueError("closed Solver in a batch")
+    return (ctypes.c_void_p * len(pool))(*[p_._h.value for p_ in pool])
+
+
+def _batch_error(pool, st):
+    for p_ in pool:
+        msg = lib().hdgmg_last_error(p_._h).decode()
+        if msg:
+            return HdgmgError(st, msg)
+    return HdgmgError(st, "batch solve failed")
+
+
+def solve_batch(pool, f_qp):
+    """hdgmg_solve_batch: the sources f_qp [nrhs][n_cells][n_q][2] spread over
+    the identical, assembled Solvers of `pool` (one HIP stream each) and
+    solved concurrently.  Returns (u [nrhs][n_cells][n_q][2], p, states
+    [nrhs][N_skel + n_cells], info dicts)."""
+    torch = pool[0].torch
+    s0 = pool[0]
+    f_qp = f_qp.detach().contiguous()
+    n = f_qp.shape[0]
+    u = torch.empty((n, s0.n_cells, s0.n_q, 2), dtype=torch.float64, device="cuda")
+    p = torch.empty((n, s0.n_cells, s0.n_q), dtype=torch.float64, device="cuda")
+    states = torch.empty((n, s0.n_skel + s0.n_cells), dtype=torch.float64, device="cuda")
+    infos = (Info * max(n, 1))()
+    torch.cuda.synchronize()  # the inputs come from the caller's stream
+    st = lib().hdgmg_solve_batch(_batch_handles(pool), len(pool), n, _ptr(f_qp), _ptr(u), _ptr(p), _ptr(states),
+                                 infos)
+    if st < 0:
+        raise _batch_error(pool, st)
+    ds = [dict(uzawa_steps=i.uzawa_steps, its=list(i.its[:i.uzawa_steps]), div_l2=i.div_l2, t_solve=i.t_solve)
+          for i in infos[:n]]
+    return u, p, states, ds
+
+
+def solve_adjoint_batch(pool, f_qp, states, gu_qp):
+    """hdgmg_solve_adjoint_batch for dJ/du = gu_qp of a batch solved by
+    solve_batch: returns (dJ/df [nrhs][n_cells][n_q][2], dJ/dnu [n_cells]
+    summed over the batch)."""
+    torch = pool[0].torch
+    s0 = pool[0]
+    f_qp, states, gu_qp = (t_.detach().contiguous() for t_ in (f_qp, states, gu_qp))
+    n = f_qp.shape[0]
+    gf = torch.empty_like(f_qp)
+    gnu = torch.zeros((len(pool), s0.n_cells), dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
-
-    def work(j):
-        s = pool[j]
-        with torch.cuda.stream(s.stream):
-            return run(s, shares[j])
-
-    if len(pool) == 1:
-        outs = [work(0)]
-    else:
-        from concurrent.futures import ThreadPoolExecutor
-        with ThreadPoolExecutor(max_workers=len(pool)) as ex:
-            outs = list(ex.map(work, range(len(pool))))
-    res = [None] * n
-    for j, idx in enumerate(shares):
-        for i, r in zip(idx, outs[j]):
-            res[i] = r
-    return res
+    st = lib().hdgmg_solve_adjoint_batch(_batch_handles(pool), len(pool), n, _ptr(f_qp), _ptr(states),
+                                         _ptr(gu_qp), _ptr(gf), _ptr(gnu), None)
+    if st < 0:
+        raise _batch_error(pool, st)
+    return gf, gnu.sum(dim=0)
 
 
 def solver_pool(n, coords, cells, n_refine, k, beta, nu, gamma, **kw):
     """n identical, assembled Solvers, each on a HIP stream of its own
-    (default priority), for stokes_solve over a batch of sources."""
+    (default priority), for solve_batch / stokes_solve over a batch of
+    sources."""
     import torch
     pool = [Solver(coords, cells, n_refine, k, beta, nu, gamma, stream=torch.cuda.Stream(), **kw)
             for _ in range(n)]

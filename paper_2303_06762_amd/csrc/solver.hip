@@ -1538,6 +1538,60 @@ hdgmg_status assemble_levels(hdgmg_ctx* ctx) {
 
 }  // namespace
 
+// Batches over several identical contexts: right-hand side i goes to
+// context i % nctx; each context works through its share on its own stream
+// in a host thread of its own, so that the contexts' latency-bound V-cycles
+// overlap on the device.
+namespace {
+hdgmg_status batch_check(hdgmg_ctx* const* ctxs, int nctx, int nrhs) {
+  if (!ctxs || nctx < 1 || nrhs < 0) return HDGMG_EINVAL;
+  for (int c = 0; c < nctx; ++c) {
+    if (!ctxs[c]) return HDGMG_EINVAL;
+    if (!ctxs[c]->assembled) {
+      ctxs[c]->err = "batch solve before hdgmg_assemble";
+      return HDGMG_ESTATE;
+    }
+    if (ctxs[c]->K.nc != ctxs[0]->K.nc || ctxs[c]->K.ndof != ctxs[0]->K.ndof || ctxs[c]->Q.nq != ctxs[0]->Q.nq) {
+      ctxs[c]->err = "batch contexts of different sizes";
+      return HDGMG_EINVAL;
+    }
+    for (int d = 0; d < c; ++d)
+      if (ctxs[d] == ctxs[c]) {
+        ctxs[c]->err = "a context appears twice in a batch";
+        return HDGMG_EINVAL;
+      }
+  }
+  return HDGMG_OK;
+}
+
+template <class F>
+hdgmg_status batch_run(hdgmg_ctx* const* ctxs, int nctx, int nrhs, F&& one) {
+  std::vector<hdgmg_status> st(nctx, HDGMG_OK);
+  auto work = [&](int c) {
+    for (int i = c; i < nrhs; i += nctx) {
+      hdgmg_status s = one(ctxs[c], i);
+      if (s < 0) {
+        st[c] = s;
+        return;
+      }
+      if (s > st[c]) st[c] = s;
+    }
+  };
+  if (nctx == 1) {
+    work(0);
+  } else {
+    std::vector<std::thread> th;
+    for (int c = 0; c < nctx; ++c) th.emplace_back(work, c);
+    for (auto& t : th) t.join();
+  }
+  hdgmg_status r = HDGMG_OK;
+  for (hdgmg_status s : st)
+    if (s < 0) return s;
+    else if (s > r) r = s;
+  return r;
+}
+}  // namespace
+
 extern "C" {
 
 void hdgmg_default_opts(hdgmg_opts* o) {
@@ -2134,6 +2188,33 @@ hdgmg_status hdgmg_solve_adjoint(hdgmg_ctx* ctx, const double* f_qp, const doubl
                 ctx->adj_f, ast));
   HIPC(hipStreamSynchronize(ctx->st));
   return result;
+}
+
+hdgmg_status hdgmg_solve_batch(hdgmg_ctx* const* ctxs, int nctx, int nrhs, const double* f_qp, double* u_qp,
+                               double* p_qp, double* states, hdgmg_info* infos) {
+  TRY(batch_check(ctxs, nctx, nrhs));
+  if (nrhs > 0 && (!f_qp || !u_qp || !p_qp)) return HDGMG_EINVAL;
+  const long nqd = (long)ctxs[0]->K.nc * ctxs[0]->Q.nq, ns = ctxs[0]->K.ndof + ctxs[0]->K.nc;
+  return batch_run(ctxs, nctx, nrhs, [&](hdgmg_ctx* ctx, int i) {
+    return hdgmg_solve(ctx, f_qp + i * nqd * 2, u_qp + i * nqd * 2, p_qp + i * nqd, states ? states + i * ns : nullptr,
+                       infos ? infos + i : nullptr);
+  });
+}
+
+hdgmg_status hdgmg_solve_adjoint_batch(hdgmg_ctx* const* ctxs, int nctx, int nrhs, const double* f_qp,
+                                       const double* states, const double* gu_qp, double* gf_qp, double* gnu,
+                                       hdgmg_info* infos) {
+  TRY(batch_check(ctxs, nctx, nrhs));
+  if (nrhs > 0 && (!f_qp || !states || !gu_qp || !gf_qp)) return HDGMG_EINVAL;
+  const long nqd = (long)ctxs[0]->K.nc * ctxs[0]->Q.nq, ns = ctxs[0]->K.ndof + ctxs[0]->K.nc;
+  const long nc = ctxs[0]->K.nc;
+  // each context accumulates into its own row of gnu (no two streams add
+  // into the same array)
+  return batch_run(ctxs, nctx, nrhs, [&](hdgmg_ctx* ctx, int i) {
+    const int c = i % nctx;
+    return hdgmg_solve_adjoint(ctx, f_qp + i * nqd * 2, states + i * ns, gu_qp + i * nqd * 2, gf_qp + i * nqd * 2,
+                               gnu ? gnu + c * nc : nullptr, nullptr, infos ? infos + i : nullptr);
+  });
 }
 
 hdgmg_status hdgmg_kernel_timer(hdgmg_ctx* ctx, int cls, int enable) {

@@ -188,3 +188,38 @@ def test_stream_pool_batch_matches_single_solver():
     for p_ in pool:
         p_.close()
     s.close()
+
+
+def test_native_batch_calls():
+    # hdgmg_solve_batch / hdgmg_solve_adjoint_batch over three contexts
+    # against one context's single solves; a context given twice is refused
+    import paper_2303_06762_amd as hd
+    c, t = synth.kuhn_square(4)
+    nr, k, beta, gamma = 1, 2, 1.0, 1e2
+    n_cells = 32 * 4 ** nr
+    nu = lognormal_nu(n_cells)
+    nq = (k + 2) ** 2
+    F = dev(synth.source_uniform(200, 5, n_cells, nq))
+    GU = dev(synth.source_uniform(300, 5, n_cells, nq))
+    _note("native batch: 5 sources over 3 contexts")
+    s = hd.Solver(c, t, nr, k, beta, nu, gamma)
+    s.assemble()
+    pool = hd.solver_pool(3, c, t, nr, k, beta, nu, gamma)
+    U, P, S, infos = hd.solve_batch(pool, F)
+    gf_b, gnu_b = hd.solve_adjoint_batch(pool, F, S, GU)
+    gnu1 = torch.zeros(n_cells, dtype=torch.float64, device="cuda")
+    for i in range(5):
+        u, p, st_, info, st = s.solve(F[i])
+        assert st == 0 and infos[i]["its"] == info["its"]
+        assert (U[i] - u).abs().max().item() <= 1e-12 * u.abs().max().item()
+        assert (P[i] - p).abs().max().item() <= 1e-12 * p.abs().max().item()
+        gf, _, _, _, st = s.solve_adjoint(F[i], st_, GU[i], gnu=gnu1)
+        assert st == 0
+        assert (gf_b[i] - gf).abs().max().item() <= 1e-12 * gf.abs().max().item()
+    assert (gnu_b - gnu1).abs().max().item() <= 1e-12 * gnu1.abs().max().item()
+    with pytest.raises(hd.HdgmgError) as e:
+        hd.solve_batch([pool[0], pool[1], pool[0]], F)
+    assert e.value.status == -1
+    for p_ in pool:
+        p_.close()
+    s.close()
