@@ -40,10 +40,10 @@ ROOF_CLASS = 1
 # HBM traffic of that kernel from two counter runs (FETCH_SIZE, then
 # WRITE_SIZE, KiB per dispatch) of `bench.py --profile-run`, each scaled by
 # what the counter read for a plain copy of 1 GiB in the same run (FETCH
-# 524308 KiB -> x2.0, WRITE 1048576 KiB -> x1.0).  Valid only for the
+# 524315 KiB -> x2.0, WRITE 1048576 KiB -> x1.0).  Valid only for the
 # workload and kernel it was taken on.
-TRAFFIC = {(2, 6, 1.0, 1e2): {"kernel": "k_cell_apply<6, double>", "fetch_KiB": 101245.78,
-                              "write_KiB": 18780.79, "fetch_scale": 1048576 / 524308.31,
+TRAFFIC = {(2, 6, 1.0, 1e2): {"kernel": "k_cell_apply<6, double>", "fetch_KiB": 96614.88,
+                              "write_KiB": 18984.96, "fetch_scale": 1048576 / 524314.69,
                               "write_scale": 1.0}}
 
 
