@@ -358,3 +358,92 @@ def test_oseen_at_sampled_facets_and_cells(oseen_setting):
     assert np.sqrt(du) <= 1e-10 * np.sqrt(un) and np.sqrt(dp) <= 1e-10 * np.sqrt(pn), (du, un, dp, pn)
     assert dv / 128 <= 1e-6 * um, (dv, um)
     s.close()
+
+
+# ---------------------------------------------------------------------------
+# The batch-gradient workload at its size: 128x128 squares (32768 cells),
+# k = 2, beta = 1, eps^-1 = 1e2, per-cell nu = exp(0.5 Z) (Z ~ N(0,1), seed
+# 3), 16 sources f_i ~ U[-1,1) (seeds 100..115), target u_t ~ U[-1,1) (seed
+# 4), J = sum_i sum_{K,q} w_q |K| |u_i - u_t|^2, FP32-storage V-cycle, the
+# batch spread over four contexts on their own HIP streams (the benchmark's
+# launch configuration).
+from oracle import adjoint  # noqa: E402
+
+AD_K, AD_NREF, AD_NRHS = 2, 5, 16
+
+
+def test_batch_gradient_at_sampled_facets_and_cells():
+    """Forward and adjoint states of every source satisfy the saddle point
+    at sampled facets (the adjoint's load: the data-rule functional of
+    dJ/du, i.e. source values dJ/du / (w_q |K|)); dJ/df at sampled cells is
+    w_q |K| u_adj(x_q) by the oracle's local recovery of the adjoint state;
+    dJ/dnu at sampled cells is -sum_i (Lift(u_i), Lift(u_adj,i))_K by the
+    oracle's local fields; and the four-context batch entry points give
+    what one context gives source by source."""
+    import paper_2303_06762_amd as hd
+    c, t = synth.kuhn_square(4)
+    _note("[fullsize adjoint] oracle hierarchy 128x128, k=2")
+    lv = mesh.hierarchy(c, t, AD_NREF)[-1]
+    n_cells, m, nq = lv.n_cells, AD_K + 1, (AD_K + 2) ** 2
+    nu = np.exp(0.5 * synth.normal(3, 0, n_cells))
+    F = np.stack([synth.source_uniform(100 + i, 1, n_cells, nq)[0] for i in range(AD_NRHS)])
+    ut = synth.source_uniform(4, 1, n_cells, nq)[0]
+    rng = np.random.default_rng(2305)
+    facets = np.sort(rng.choice(np.flatnonzero(lv.int_id >= 0), N_FACETS, replace=False))
+    cells = np.sort(rng.choice(n_cells, N_CELLS, replace=False))
+    need = sorted(set(lv.facet_cells[facets].ravel().tolist()) | set(cells.tolist()))
+    elems = {K: hdg.Element(lv, K, AD_K, nu[K], 1.0) for K in need}
+    gidx = {}
+    for K in need:
+        g = -np.ones(6 * m, dtype=np.int64)
+        for i in range(3):
+            fi = lv.int_id[lv.cell_facets[K, i]]
+            if fi >= 0:
+                for comp in range(2):
+                    for j in range(m):
+                        g[hdg.lam_index(AD_K, i, comp, j)] = (fi * 2 + comp) * m + j
+        gidx[K] = g
+    S = dict(lv=lv, facets=facets, elems=elems, gidx=gidx, m=m)
+
+    _note("[fullsize adjoint] pool of four contexts, batch forward + adjoint")
+    pool = hd.solver_pool(4, c, t, AD_NREF, AD_K, 1.0, nu, 1e2, vcycle_precision=1)
+    s = pool[0]
+    W = host(s.data_weights())
+    for K in need:
+        assert np.abs(W[K] - elems[K].wq).max() <= 1e-15
+    Fd = dev(F)
+    u, p, states, infos = hd.solve_batch(pool, Fd)
+    assert all(0 < d["uzawa_steps"] < 50 for d in infos), infos
+    gu = 2.0 * dev(W)[None, :, :, None] * (u - dev(ut)[None])
+    gf, gnu = hd.solve_adjoint_batch(pool, Fd, states, gu)
+    u, states, gu, gf, gnu = host(u), host(states), host(gu), host(gf), host(gnu)
+    gnu_o = np.zeros(len(cells))
+    gnu_1 = None
+    for b in range(AD_NRHS):
+        lam, p0 = states[b, :s.n_skel], states[b, s.n_skel:]
+        f_adj = gu[b] / W[:, :, None]
+        gf_b, gnu_1, adj, info, st = s.solve_adjoint(dev(F[b]), dev(states[b]), dev(gu[b]),
+                                                     gnu=None if gnu_1 is None else gnu_1)
+        assert st == 0, (b, info)
+        assert np.abs(host(gf_b) - gf[b]).max() <= 1e-10 * np.abs(gf[b]).max(), b
+        adj = host(adj)
+        lam_a, p0_a = adj[:s.n_skel], adj[s.n_skel:]
+        for vec, pv, src in ((lam, p0, F[b]), (lam_a, p0_a, f_adj)):
+            g_o = _sampled_rows(S, lambda K, e: e.load(src[K]))
+            r = _sampled_rows(S, lambda K, e: e.S @ _local(S, vec, K) - pv[K] * e.d - e.load(src[K]))
+            scale = np.sqrt(np.mean(g_o ** 2))
+            assert np.abs(r).max() <= 1e-4 * scale, (b, np.abs(r).max(), scale)
+        d2 = n2 = 0.0
+        for i_, K in enumerate(cells):
+            e = elems[K]
+            ua, _, _, _ = e.recover(_local(S, lam_a, K), p0_a[K], f_adj[K])
+            ref = W[K][:, None] * ua
+            d2 += np.sum((gf[b, K] - ref) ** 2)
+            n2 += np.sum(ref ** 2)
+            gnu_o[i_] += adjoint.grad_nu_cell(e, _local(S, lam, K), F[b, K], _local(S, lam_a, K), f_adj[K])
+        assert np.sqrt(d2) <= 1e-10 * np.sqrt(n2), (b, d2, n2)
+    gnu_1 = host(gnu_1)
+    assert np.abs(gnu_1 - gnu).max() <= 1e-10 * np.abs(gnu).max()
+    assert np.linalg.norm(gnu[cells] - gnu_o) <= 1e-10 * np.linalg.norm(gnu_o), (gnu[cells][:4], gnu_o[:4])
+    for p_ in pool:
+        p_.close()
