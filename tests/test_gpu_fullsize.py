@@ -447,3 +447,74 @@ def test_batch_gradient_at_sampled_facets_and_cells():
     assert np.linalg.norm(gnu[cells] - gnu_o) <= 1e-10 * np.linalg.norm(gnu_o), (gnu[cells][:4], gnu_o[:4])
     for p_ in pool:
         p_.close()
+
+
+def _sample(lv, k, nu, beta, seed):
+    """Sampled interior facets and cells, the oracle's cells around them and
+    their cell-local -> global skeleton maps."""
+    m = k + 1
+    rng = np.random.default_rng(seed)
+    facets = np.sort(rng.choice(np.flatnonzero(lv.int_id >= 0), N_FACETS, replace=False))
+    cells = np.sort(rng.choice(lv.n_cells, N_CELLS, replace=False))
+    need = sorted(set(lv.facet_cells[facets].ravel().tolist()) | set(cells.tolist()))
+    nus = np.broadcast_to(np.asarray(nu, float), (lv.n_cells,))
+    elems = {K: hdg.Element(lv, K, k, nus[K], beta) for K in need}
+    gidx = {}
+    for K in need:
+        g = -np.ones(6 * m, dtype=np.int64)
+        for i in range(3):
+            fi = lv.int_id[lv.cell_facets[K, i]]
+            if fi >= 0:
+                for comp in range(2):
+                    for j in range(m):
+                        g[hdg.lam_index(k, i, comp, j)] = (fi * 2 + comp) * m + j
+        gidx[K] = g
+    return dict(lv=lv, facets=facets, cells=cells, elems=elems, gidx=gidx, m=m)
+
+
+@pytest.mark.parametrize("k,beta,gamma,prec", [(1, 0.0, 1e4, 1), (3, 1e3, 1e2, 1), (4, 1.0, 1e2, 0),
+                                               (2, 1.0, 1.0, 2)])
+def test_orders_and_parameters_at_256x256(k, beta, gamma, prec):
+    """Other corners of the 256x256 Stokes sweep (k, beta, gamma and V-cycle
+    storage): the residual of the inner solve A^eps x = g at sampled facets;
+    for gamma >= 1e2 also the saddle-point residual of the full AL-Uzawa
+    solve and the local recovery at sampled cells, against the oracle's
+    per-cell condensation.  (At gamma = 1 the Uzawa iteration contracts by
+    only ~0.6 per step, Sec. 2.3, and would need far more than its cap of
+    50 steps.)"""
+    import paper_2303_06762_amd as hd
+    c, t = synth.kuhn_square(4)
+    _note(f"[fullsize sweep] k={k} beta={beta} gamma={gamma} prec={prec}")
+    lv = mesh.hierarchy(c, t, NREF)[-1]
+    nq = (k + 2) ** 2
+    S = _sample(lv, k, 1.0, beta, 2306 + k)
+    s = hd.Solver(c, t, NREF, k, beta, 1.0, gamma, atol=0.0, vcycle_precision=prec)
+    s.assemble()
+    assert s.n_skel == lv.n_int * 2 * (k + 1)
+    f = synth.source_uniform(0, 1, lv.n_cells, nq)[0]
+    g_o = _sampled_rows(S, lambda K, e: e.load(f[K]))
+    scale = np.sqrt(np.mean(g_o ** 2))
+    x, its, rel, st = s.inner_solve(s.rhs(dev(f)))
+    assert st == 0 and rel <= 1e-8, (st, rel, its)
+    x = host(x)
+    r = g_o - _sampled_rows(S, lambda K, e: e.S @ _local(S, x, K) + gamma / e.area * e.d * (e.d @ _local(S, x, K)))
+    assert np.abs(r).max() <= 1e-4 * scale, (np.abs(r).max(), scale)
+    if gamma < 1e2:
+        s.close()
+        return
+    u, p, state, info, st = s.solve(dev(f))
+    assert st == 0, info
+    state = host(state)
+    lam, p0 = state[:s.n_skel], state[s.n_skel:]
+    r = _sampled_rows(S, lambda K, e: e.S @ _local(S, lam, K) - p0[K] * e.d - e.load(f[K]))
+    assert np.abs(r).max() <= 1e-4 * scale, (np.abs(r).max(), scale)
+    ug, pg = host(u), host(p)
+    du = un = dp = pn = 0.0
+    for K in S["cells"]:
+        uo, po, _, _ = S["elems"][K].recover(_local(S, lam, K), p0[K], f[K])
+        du += np.sum((ug[K] - uo) ** 2)
+        un += np.sum(uo ** 2)
+        dp += np.sum((pg[K] - po) ** 2)
+        pn += np.sum(po ** 2)
+    assert np.sqrt(du) <= 1e-10 * np.sqrt(un) and np.sqrt(dp) <= 1e-10 * np.sqrt(pn), (du, un, dp, pn)
+    s.close()
