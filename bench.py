@@ -331,8 +331,9 @@ def main():
                          "counters) then two FP64 inner solves; prints a summary only")
     a = ap.parse_args()
     if a.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {a.gpus} is not supported "
-              "(see the sharding notes in DESIGN.md).", file=sys.stderr)
+        print(f"bench.py: the solver runs on one GPU; --gpus {a.gpus} is not supported "
+              "(a context holds the whole mesh; sharding across GPUs is not implemented).",
+              file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
