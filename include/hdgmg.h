@@ -391,7 +391,11 @@ hdgmg_status hdgmg_export(const hdgmg_ctx* ctx, int what, int level, void* dst,
 
 /* Live kernel timing for roofline measurements.  While enabled for a
  * kernel class, every launch of that class on the context's stream is
- * bracketed by a pair of HIP events; hdgmg_kernel_timer_read synchronises
+ * timed by a pair of HIP events (the order-k cell apply and patch
+ * relaxation launch through hipExtLaunchKernelGGL, whose dispatch records
+ * the pair around the kernel itself; other launches are bracketed by event
+ * records), and the preconditioner runs eagerly instead of as a graph
+ * replay unless only class 3 is enabled; hdgmg_kernel_timer_read synchronises
  * the stream and returns the summed elapsed time (ms), the number of
  * launches and the summed algorithmic bytes of those launches (the bytes
  * the launch must move given the stored operators: every matrix entry it

@@ -24,6 +24,7 @@
 //        four 16-patch runs per step
 // A Gauss-Seidel colour phase is a cell apply (y = S x for every cell) then
 // k_patch_relax (x_s += A_ss^-1 (b - y)_s for the colour's patches).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "fast.hpp"
@@ -385,15 +386,25 @@ __global__ void k_patches_sym_f16(int np, int m2, const double* __restrict__ Pp,
 
 inline int nblk(long n, int t = 256) { return (int)((n + t - 1) / t); }
 
+// A launch on st, through hipExtLaunchKernelGGL with ev's start / stop
+// events when ev is given.
+#define LAUNCH_EV(KERNEL, GRID, BLOCK, ...)                                                        \
+  do {                                                                                             \
+    if (ev)                                                                                        \
+      hipExtLaunchKernelGGL(KERNEL, GRID, BLOCK, 0, st, ev->start, ev->stop, 0, __VA_ARGS__);      \
+    else                                                                                           \
+      hipLaunchKernelGGL(KERNEL, GRID, BLOCK, 0, st, __VA_ARGS__);                                 \
+  } while (0)
+
 template <typename TS>
 void cell_apply_t(hipStream_t st, int m2, int nc, const TS* Sp, const int* cdof, const double* x, double* yF,
-                  bool full, const float4* sc) {
+                  bool full, const float4* sc, const KernelEvents* ev) {
   if (!fast_cell_packed(3 * m2, full)) {
     switch (m2) {
 #define CASE(M)                                                                                        \
   case M:                                                                                              \
-    hipLaunchKernelGGL((k_cell_apply_rows<M, TS>), dim3((nc + 256 / (3 * M) - 1) / (256 / (3 * M))),   \
-                       dim3(256), 0, st, nc, Sp, cdof, x, yF);                                         \
+    LAUNCH_EV((k_cell_apply_rows<M, TS>), dim3((nc + 256 / (3 * M) - 1) / (256 / (3 * M))), dim3(256), \
+              nc, Sp, cdof, x, yF);                                                            \
     break;
       CASE(2) CASE(4) CASE(6) CASE(8) CASE(10)
 #undef CASE
@@ -403,7 +414,7 @@ void cell_apply_t(hipStream_t st, int m2, int nc, const TS* Sp, const int* cdof,
   switch (m2) {
 #define CASE(M)                                                                                  \
   case M:                                                                                        \
-    hipLaunchKernelGGL((k_cell_apply<M, TS>), dim3(nblk(nc)), dim3(256), 0, st, nc, Sp, cdof, x, yF, sc); \
+    LAUNCH_EV((k_cell_apply<M, TS>), dim3(nblk(nc)), dim3(256), nc, Sp, cdof, x, yF, sc); \
     break;
     CASE(2) CASE(4) CASE(6)
 #undef CASE
@@ -412,17 +423,17 @@ void cell_apply_t(hipStream_t st, int m2, int nc, const TS* Sp, const int* cdof,
 
 template <typename TS>
 void patch_relax_t(hipStream_t st, int m2, int np, const int* pf, const TS* Pp, const double* b, const double* yF,
-                   double* x, bool full, const float* sc) {
+                   double* x, bool full, const float* sc, const KernelEvents* ev) {
   if (!full) {
     switch (m2) {
 #define CASE(M)                                                                                                \
   case M:                                                                                                      \
     if (yF)                                                                                                    \
-      hipLaunchKernelGGL((k_patch_relax_wave<M, TS, true>), dim3((np + WaveShape<M>::PPW - 1) / WaveShape<M>::PPW), \
-                         dim3(64), 0, st, np, pf, Pp, b, yF, x, sc);                                          \
+      LAUNCH_EV((k_patch_relax_wave<M, TS, true>), dim3((np + WaveShape<M>::PPW - 1) / WaveShape<M>::PPW),     \
+                dim3(64), np, pf, Pp, b, yF, x, sc);                                                          \
     else                                                                                                       \
-      hipLaunchKernelGGL((k_patch_relax_wave<M, TS, false>), dim3((np + WaveShape<M>::PPW - 1) / WaveShape<M>::PPW), \
-                         dim3(64), 0, st, np, pf, Pp, b, yF, x, sc);                                          \
+      LAUNCH_EV((k_patch_relax_wave<M, TS, false>), dim3((np + WaveShape<M>::PPW - 1) / WaveShape<M>::PPW),    \
+                dim3(64), np, pf, Pp, b, yF, x, sc);                                                          \
     break;
       CASE(2) CASE(4) CASE(6) CASE(8) CASE(10)
 #undef CASE
@@ -432,27 +443,29 @@ void patch_relax_t(hipStream_t st, int m2, int np, const int* pf, const TS* Pp, 
   switch (m2) {
 #define CASE(M)                                                                                            \
   case M:                                                                                                  \
-    hipLaunchKernelGGL((k_patch_relax<M, TS>), dim3((np + 256 / (6 * M) - 1) / (256 / (6 * M))), dim3(256), 0, \
-                       st, np, pf, Pp, b, yF, x, sc);                                                   \
+    LAUNCH_EV((k_patch_relax<M, TS>), dim3((np + 256 / (6 * M) - 1) / (256 / (6 * M))), dim3(256), np, pf, Pp, \
+              b, yF, x, sc);                                                                               \
     break;
     CASE(2) CASE(4) CASE(6) CASE(8) CASE(10)
 #undef CASE
   }
 }
 
+#undef LAUNCH_EV
+
 }  // namespace
 
 template <typename TS>
 void launch_cell_apply(hipStream_t st, int m2, int nc, const TS* Sp, const int* cdof, const double* x,
-                       double* yF, bool full, const float4* al) {
-  if (nc > 0) cell_apply_t<TS>(st, m2, nc, Sp, cdof, x, yF, full, al);
+                       double* yF, bool full, const float4* al, const KernelEvents* ev) {
+  if (nc > 0) cell_apply_t<TS>(st, m2, nc, Sp, cdof, x, yF, full, al, ev);
 }
 template void launch_cell_apply<double>(hipStream_t, int, int, const double*, const int*, const double*, double*,
-                                        bool, const float4*);
+                                        bool, const float4*, const KernelEvents*);
 template void launch_cell_apply<float>(hipStream_t, int, int, const float*, const int*, const double*, double*,
-                                       bool, const float4*);
+                                       bool, const float4*, const KernelEvents*);
 template void launch_cell_apply<_Float16>(hipStream_t, int, int, const _Float16*, const int*, const double*,
-                                          double*, bool, const float4*);
+                                          double*, bool, const float4*, const KernelEvents*);
 
 void launch_facet_sum(hipStream_t st, int nint, int m2, const double* yF, const double* b, double alpha,
                       double* y) {
@@ -462,15 +475,15 @@ void launch_facet_sum(hipStream_t st, int nint, int m2, const double* yF, const 
 
 template <typename TS>
 void launch_patch_relax(hipStream_t st, int m2, int np, const int* pf, const TS* Pp, const double* b,
-                        const double* yF, double* x, bool full, const float* sc) {
-  if (np > 0) patch_relax_t<TS>(st, m2, np, pf, Pp, b, yF, x, full, sc);
+                        const double* yF, double* x, bool full, const float* sc, const KernelEvents* ev) {
+  if (np > 0) patch_relax_t<TS>(st, m2, np, pf, Pp, b, yF, x, full, sc, ev);
 }
 template void launch_patch_relax<double>(hipStream_t, int, int, const int*, const double*, const double*,
-                                         const double*, double*, bool, const float*);
+                                         const double*, double*, bool, const float*, const KernelEvents*);
 template void launch_patch_relax<float>(hipStream_t, int, int, const int*, const float*, const double*,
-                                        const double*, double*, bool, const float*);
+                                        const double*, double*, bool, const float*, const KernelEvents*);
 template void launch_patch_relax<_Float16>(hipStream_t, int, int, const int*, const _Float16*, const double*,
-                                           const double*, double*, bool, const float*);
+                                           const double*, double*, bool, const float*, const KernelEvents*);
 
 void launch_cells_f16(hipStream_t st, int nc, int m2, const double* Sp, const int* cdof, const double* cdiv,
                       const double* area, double eps_inv, _Float16* Sp16, float4* al) {

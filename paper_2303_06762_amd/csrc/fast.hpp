@@ -36,9 +36,16 @@ inline long fast_patch_words(int m2, bool full) {
 // per facet component x 2 components).
 // TS = _Float16 (packed blocks only): al[K] = (s, c0, c1, c2) as
 // launch_cells_f16 writes it; else al is null.
+// ev: when given, the launch records ev->start and ev->stop as part of its
+// dispatch (hipExtLaunchKernelGGL), so that their interval is the kernel's
+// own execution; eager launches only (timers are off under graph capture).
+struct KernelEvents {
+  hipEvent_t start, stop;
+};
 template <typename TS>
 void launch_cell_apply(hipStream_t st, int m2, int nc, const TS* Sp, const int* cdof, const double* x,
-                       double* yF, bool full = false, const float4* al = nullptr);
+                       double* yF, bool full = false, const float4* al = nullptr,
+                       const KernelEvents* ev = nullptr);
 // y = b + alpha * (y_F[side 0] + y_F[side 1]) (b may be null)
 void launch_facet_sum(hipStream_t st, int nint, int m2, const double* yF, const double* b, double alpha,
                       double* y);
@@ -47,7 +54,8 @@ void launch_facet_sum(hipStream_t st, int nint, int m2, const double* yF, const 
 // inverses, else null); yF null: y = 0
 template <typename TS>
 void launch_patch_relax(hipStream_t st, int m2, int np, const int* pf, const TS* Pp, const double* b,
-                        const double* yF, double* x, bool full = true, const float* sc = nullptr);
+                        const double* yF, double* x, bool full = true, const float* sc = nullptr,
+                        const KernelEvents* ev = nullptr);
 void launch_pack_cells(hipStream_t st, int nc, int nK, const double* S, double* Sp, bool full = false);
 // FP32 copy of packed blocks (pair groups -> quad groups).
 void launch_regroup_cells_f32(hipStream_t st, int nc, int nK, const double* Sp, float* Sp32);

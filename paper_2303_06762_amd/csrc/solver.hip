@@ -334,6 +334,34 @@ void kt_end(hdgmg_ctx* ctx, int cls, int idx, double bytes) {
   T.bytes += bytes;
 }
 
+// A timed launch whose events the dispatch itself records (launchers taking
+// a KernelEvents*): the interval excludes the event packets that kt_begin /
+// kt_end put around a launch.  Returns the events to pass, or null when the
+// class is not timed; kd_end adds the launch's bytes.
+struct KtDispatch {
+  int idx = -1;
+  KernelEvents ev{};
+  const KernelEvents* ptr() const { return idx < 0 ? nullptr : &ev; }
+};
+KtDispatch kd_begin(hdgmg_ctx* ctx, int cls) {
+  KtDispatch d;
+  auto& T = ctx->timers[cls];
+  if (!T.on) return d;
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess) return d;
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return d;
+  }
+  T.ev.push_back({a, b});
+  d.idx = (int)T.ev.size() - 1;
+  d.ev = {a, b};
+  return d;
+}
+void kd_end(hdgmg_ctx* ctx, int cls, const KtDispatch& d, double bytes) {
+  if (d.idx >= 0) ctx->timers[cls].bytes += bytes;
+}
+
 void kt_clear(hdgmg_ctx::KTimer& T) {
   for (auto& e : T.ev) {
     (void)hipEventDestroy(e.first);
@@ -569,27 +597,30 @@ void sweep(hdgmg_ctx* ctx, DevLevel& D, double* x, const double* b, bool forward
     } else if (D.fast) {
       // colour phase = cell apply (all cells) + patch relaxation (colour c)
       const bool skip = x_zero && i == 0;
-      int t;
       if (!skip) {
-        t = kt_begin(ctx, level < 0 ? 1 : 2);
+        const int ccls = level < 0 ? 1 : 2;
+        const KtDispatch kd = kd_begin(ctx, ccls);
         if (D.f16)
-          launch_cell_apply<_Float16>(ctx->st, 2 * D.m, D.nc, D.Sp16, D.cdof, x, D.yF, false, D.al16);
+          launch_cell_apply<_Float16>(ctx->st, 2 * D.m, D.nc, D.Sp16, D.cdof, x, D.yF, false, D.al16, kd.ptr());
         else if (D.f32)
-          launch_cell_apply<float>(ctx->st, 2 * D.m, D.nc, D.Sp32, D.cdof, x, D.yF, D.full);
+          launch_cell_apply<float>(ctx->st, 2 * D.m, D.nc, D.Sp32, D.cdof, x, D.yF, D.full, nullptr, kd.ptr());
         else
-          launch_cell_apply<double>(ctx->st, 2 * D.m, D.nc, D.Sp, D.cdof, x, D.yF, D.full);
-        kt_end(ctx, level < 0 ? 1 : 2, t, D.bytes_cell_vc);
+          launch_cell_apply<double>(ctx->st, 2 * D.m, D.nc, D.Sp, D.cdof, x, D.yF, D.full, nullptr, kd.ptr());
+        kd_end(ctx, ccls, kd, D.bytes_cell_vc);
       }
       const double* yF = skip ? nullptr : D.yF;
-      t = kt_begin(ctx, level < 0 ? 0 : 2);
+      const int rcls = level < 0 ? 0 : 2;
+      const KtDispatch kr = kd_begin(ctx, rcls);
       if (D.f16)
         launch_patch_relax<_Float16>(ctx->st, 2 * D.m, D.npc[c], D.pfc[c], D.Pp16[c], b, yF, x, D.pfull,
-                                     D.psc16[c]);
+                                     D.psc16[c], kr.ptr());
       else if (D.f32)
-        launch_patch_relax<float>(ctx->st, 2 * D.m, D.npc[c], D.pfc[c], D.Pp32[c], b, yF, x, D.pfull);
+        launch_patch_relax<float>(ctx->st, 2 * D.m, D.npc[c], D.pfc[c], D.Pp32[c], b, yF, x, D.pfull, nullptr,
+                                  kr.ptr());
       else
-        launch_patch_relax<double>(ctx->st, 2 * D.m, D.npc[c], D.pfc[c], D.Ppc[c], b, yF, x, D.pfull);
-      kt_end(ctx, level < 0 ? 0 : 2, t, D.bytes_relax_vc[c]);
+        launch_patch_relax<double>(ctx->st, 2 * D.m, D.npc[c], D.pfc[c], D.Ppc[c], b, yF, x, D.pfull, nullptr,
+                                   kr.ptr());
+      kd_end(ctx, rcls, kr, D.bytes_relax_vc[c]);
     } else {
       const int cls = level < 0 ? 0 : 2;
       int t = kt_begin(ctx, cls);
@@ -608,14 +639,14 @@ void level_apply(hdgmg_ctx* ctx, DevLevel& D, const double* x, double* y, double
                  int cls, bool vc) {
   const bool f32 = vc && D.f32;
   if (D.fast) {
-    int t = kt_begin(ctx, cls);
+    const KtDispatch kd = kd_begin(ctx, cls);
     if (vc && D.f16)
-      launch_cell_apply<_Float16>(ctx->st, 2 * D.m, D.nc, D.Sp16, D.cdof, x, D.yF, false, D.al16);
+      launch_cell_apply<_Float16>(ctx->st, 2 * D.m, D.nc, D.Sp16, D.cdof, x, D.yF, false, D.al16, kd.ptr());
     else if (f32)
-      launch_cell_apply<float>(ctx->st, 2 * D.m, D.nc, D.Sp32, D.cdof, x, D.yF, D.full);
+      launch_cell_apply<float>(ctx->st, 2 * D.m, D.nc, D.Sp32, D.cdof, x, D.yF, D.full, nullptr, kd.ptr());
     else
-      launch_cell_apply<double>(ctx->st, 2 * D.m, D.nc, D.Sp, D.cdof, x, D.yF, D.full);
-    kt_end(ctx, cls, t, f32 ? D.bytes_cell_vc : D.bytes_cell);
+      launch_cell_apply<double>(ctx->st, 2 * D.m, D.nc, D.Sp, D.cdof, x, D.yF, D.full, nullptr, kd.ptr());
+    kd_end(ctx, cls, kd, f32 ? D.bytes_cell_vc : D.bytes_cell);
     launch_facet_sum(ctx->st, D.nint, 2 * D.m, D.yF, b, alpha, y);
   } else {
     int t = kt_begin(ctx, cls);

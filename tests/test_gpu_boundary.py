@@ -132,3 +132,40 @@ def test_pressure_robustness_at_128x128():
     du3 = np.sqrt(np.sum(W[..., None] * (u3.cpu().numpy() - u1) ** 2))
     assert du3 >= 1e-2 * unorm, (du3, unorm)
     s.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_kernel_timers_leave_results_unchanged(prec):
+    # hdgmg_kernel_timer: with the per-kernel timers on, the order-k cell
+    # apply and patch relaxation are launched with dispatch-recorded events
+    # and the other classes between event records, eagerly; the inner solve
+    # must give the same iterate and count as the graph-replayed solve, and
+    # every class must report launches, time and bytes.
+    import paper_2303_06762_amd as hd
+    print(f"kernel timers prec={prec}", flush=True)
+    c, t = synth.kuhn_square(4)
+    s = hd.Solver(c, t, 3, 2, 1.0, 1.0, 1e2, stream_dofs=0, vcycle_precision=prec)
+    s.assemble()
+    f = dev(synth.source_uniform(1, 1, s.n_cells, s.n_q)[0])
+    g = s.rhs(f)
+    x0, its0, _, st0 = s.inner_solve(g)
+    x0 = x0.clone()
+    for cls in range(5):
+        s.timer(cls, True)
+    x1, its1, _, st1 = s.inner_solve(g)
+    torch.cuda.synchronize()
+    reads = {cls: s.timer_read(cls) for cls in range(5)}
+    for cls in range(5):
+        s.timer(cls, False)
+    assert st0 == 0 and st1 == 0 and its1 == its0
+    assert (x1 - x0).abs().max().item() <= 1e-12 * x0.abs().max().item()
+    for cls in (0, 1):
+        ms, n, b = reads[cls]
+        assert n > 0 and ms > 0.0 and b > 0.0, (cls, reads[cls])
+    # the lowest-order levels: launched phases (class 2) or, on this small
+    # hierarchy, all inside the tabulated coarse operator (class 4)
+    assert reads[2][1] + reads[4][1] > 0 and reads[4][0] > 0.0, reads
+    # the cell apply runs once per colour phase after the first and once per
+    # Krylov product: at least its launches
+    assert reads[1][1] >= its1
+    s.close()
