@@ -315,7 +315,7 @@ def main():
     ap.add_argument("--n-refine", type=int, default=6)
     ap.add_argument("--beta", type=float, default=1.0)
     ap.add_argument("--gamma", type=float, default=1e2)
-    ap.add_argument("--cpu-reps", type=int, default=5)
+    ap.add_argument("--cpu-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oseen", action="store_true", help="skip the lid-driven cavity Picard workload")
     ap.add_argument("--picard-steps", type=int, default=10)
