@@ -163,8 +163,11 @@ typedef struct {
  * alloc returns `bytes` bytes of device memory aligned to at least 256 bytes,
  * or NULL on failure; free releases a pointer alloc returned.  Both are
  * called on the thread that called the library, only from hdgmg_setup,
- * hdgmg_assemble, hdgmg_solve_adjoint (its first call) and hdgmg_destroy,
- * after the context's stream has been synchronised for frees. */
+ * hdgmg_assemble, hdgmg_set_newton (its first call), hdgmg_solve_adjoint and
+ * hdgmg_solve_adjoint_batch (the first adjoint solve of a context; the batch
+ * allocates for every context before its worker threads start) and
+ * hdgmg_destroy, after the context's stream has been synchronised for
+ * frees. */
 typedef void* (*hdgmg_alloc_fn)(size_t bytes, void* alloc_ctx);
 typedef void (*hdgmg_free_fn)(void* ptr, void* alloc_ctx);
 

@@ -2182,6 +2182,18 @@ hdgmg_status hdgmg_solve_x0(hdgmg_ctx* ctx, const double* f_qp, const double* x0
   return result;
 }
 
+// Buffers of the adjoint solve, allocated at its first call on the calling
+// thread (the batch entry point calls this before it starts its workers, so
+// that the caller's allocator only runs on the caller's thread).
+static hdgmg_status adjoint_buffers(hdgmg_ctx* ctx) {
+  if (ctx->adj_f) return HDGMG_OK;
+  const long nqd = (long)ctx->K.nc * ctx->Q.nq;
+  TRY(dalloc(ctx, &ctx->adj_f, (size_t)nqd * 2));
+  TRY(dalloc(ctx, &ctx->adj_p, (size_t)nqd));
+  TRY(dalloc(ctx, &ctx->adj_state, (size_t)(ctx->K.ndof + ctx->K.nc)));
+  return HDGMG_OK;
+}
+
 hdgmg_status hdgmg_solve_adjoint(hdgmg_ctx* ctx, const double* f_qp, const double* state, const double* gu_qp,
                                  double* gf_qp, double* gnu, double* adj_state, hdgmg_info* info) {
   if (!ctx || !f_qp || !state || !gu_qp || !gf_qp) return HDGMG_EINVAL;
@@ -2194,12 +2206,7 @@ hdgmg_status hdgmg_solve_adjoint(hdgmg_ctx* ctx, const double* f_qp, const doubl
     return HDGMG_ESTATE;
   }
   const DevLevel& KL = ctx->K;
-  const long nqd = (long)KL.nc * ctx->Q.nq;
-  if (!ctx->adj_f) {
-    TRY(dalloc(ctx, &ctx->adj_f, (size_t)nqd * 2));
-    TRY(dalloc(ctx, &ctx->adj_p, (size_t)nqd));
-    TRY(dalloc(ctx, &ctx->adj_state, (size_t)(KL.ndof + KL.nc)));
-  }
+  TRY(adjoint_buffers(ctx));
   double* ast = adj_state ? adj_state : ctx->adj_state;
   // the adjoint load v -> sum gu . v(x_q) is the forward load of gu / (w_q |K|)
   launch_data_weight(ctx->st, ctx->Q, KL.X, KL.cells, KL.nc, gu_qp, 1, ctx->adj_f);
@@ -2239,6 +2246,10 @@ hdgmg_status hdgmg_solve_adjoint_batch(hdgmg_ctx* const* ctxs, int nctx, int nrh
   if (nrhs > 0 && (!f_qp || !states || !gu_qp || !gf_qp)) return HDGMG_EINVAL;
   const long nqd = (long)ctxs[0]->K.nc * ctxs[0]->Q.nq, ns = ctxs[0]->K.ndof + ctxs[0]->K.nc;
   const long nc = ctxs[0]->K.nc;
+  for (int c = 0; c < nctx && nrhs > 0; ++c) {
+    hdgmg_status s = adjoint_buffers(ctxs[c]);
+    if (s != HDGMG_OK) return s;
+  }
   // each context accumulates into its own row of gnu (no two streams add
   // into the same array)
   return batch_run(ctxs, nctx, nrhs, [&](hdgmg_ctx* ctx, int i) {
