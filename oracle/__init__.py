@@ -17,6 +17,15 @@ Layout (sections, equations and algorithms of Fu & Kuang, arXiv 2303.06762):
           MG_hp (Alg. 2)
   krylov  flexible CG and AL-Uzawa (stOpEq-ALU)
   solver  end-to-end drivers R1 (direct) and R2 (the method)
+Tetrahedral meshes (the same scheme and method in three dimensions):
+  mesh3d    nested Kuhn / Bey-refined tetrahedral meshes, faces, edges,
+            edge patches and their colouring
+  hdg3d     local solver + static condensation on tetrahedra (face basis,
+            tangential components in the face frame), R1, uncondensed solve
+  cr3d      closed-form lowest-order block on tetrahedra (Thm 3.1)
+  mg3d      edge-patch block Gauss-Seidel, averaging + harmonic-extension
+            transfers at face centroids, MG_h (Alg. 1), MG_hp (Alg. 2)
+  solver3d  end-to-end drivers R1 and R2 on tetrahedra
 
 Parity status of each function is stated in its docstring; every function
 is pinned by a CPU test unless it says "parity unpinned".

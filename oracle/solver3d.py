@@ -1,0 +1,37 @@
+"""End-to-end oracle drivers on tetrahedral meshes (test infrastructure only).
+
+R1: the discrete solution by a direct solve of the condensed saddle point.
+R2: the method: AL-Uzawa outer loop (stOpEq-ALU), flexible CG inner solve
+    (x0 = 0 for every Uzawa step), preconditioned by MG_hp (Alg. 2) whose
+    auxiliary solver is MG_h (Alg. 1) on the lowest-order CR-equivalent
+    operators of all levels, with edge-patch block Gauss-Seidel for the
+    order-k relaxation and the lowest-order smoothing (m_p = m_h = 2 by
+    default, the smallest count of the paper's three-dimensional runs).
+"""
+import numpy as np
+
+from . import mesh3d, hdg3d, mg3d, krylov
+
+
+class Setup3:
+    def __init__(self, coords, cells, n_refine, k, nu, beta, gamma,
+                 m_p=2, m_h=2, q=1, growth=2, harmonic=True):
+        self.levels = mesh3d.hierarchy(coords, cells, n_refine)
+        self.lv = self.levels[-1]
+        self.k = k
+        self.prob = hdg3d.Problem3(self.lv, k, nu, beta, gamma)
+        self.Aeps = self.prob.matrix_Aeps().tocsr()
+        self.D = self.prob.matrix_D().tocsr()
+        self.eps_inv = self.prob.eps_inv
+        self.hier = mg3d.Hierarchy3(self.levels, self.prob.nu_c, beta, self.eps_inv, harmonic=harmonic)
+        self.prec = mg3d.HPMG3(self.Aeps, self.lv, k, self.hier, m_p, m_h, q, growth)
+
+    def inner(self, b, rtol=1e-8, atol=1e-10, max_it=500):
+        return krylov.fcg(self.Aeps, b, self.prec, rtol, atol, max_it)
+
+    def solve(self, f_qp, rtol=1e-8, atol=1e-10, max_it=500, uzawa_max=50, uzawa_tol=1e-10):
+        g = self.prob.rhs(f_qp)
+        lam, p0, log = krylov.uzawa(self.Aeps, self.D, self.lv.volume, g, self.eps_inv,
+                                    lambda b: self.inner(b, rtol, atol, max_it),
+                                    uzawa_max, uzawa_tol)
+        return dict(g=g, lam=lam, p0=p0, its=[l[0] for l in log], hist=[l[1] for l in log])

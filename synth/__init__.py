@@ -72,6 +72,33 @@ def kuhn_square(n):
     return coords, np.asarray(cells, dtype=np.int32)
 
 
+def kuhn_cube(n):
+    """Structured tetrahedral mesh of [0,1]^3 with n^3 cubes, each split into
+    the six tetrahedra of its Kuhn (Freudenthal) subdivision.
+
+    Vertex (i,j,l) has index i + (n+1) j + (n+1)^2 l.  Cube (i,j,l) (index
+    i + n j + n^2 l) yields one tetrahedron per permutation (a,b,c) of the
+    axes (0,1,2), in lexicographic order of the permutation: the vertex path
+    base, base + e_a, base + e_a + e_b, base + (1,1,1).  Returns (coords
+    [nv,3] float64, cells [nc,4] int32)."""
+    xs = np.linspace(0.0, 1.0, n + 1)
+    Z, Y, X = np.meshgrid(xs, xs, xs, indexing="ij")
+    coords = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    perms = [(0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)]
+    cells = []
+    for l in range(n):
+        for j in range(n):
+            for i in range(n):
+                for p in perms:
+                    pos = [i, j, l]
+                    path = [tuple(pos)]
+                    for ax in p:
+                        pos[ax] += 1
+                        path.append(tuple(pos))
+                    cells.append([a + (n + 1) * b + (n + 1) ** 2 * c for a, b, c in path])
+    return coords, np.asarray(cells, dtype=np.int32)
+
+
 def source_uniform(seed, nrhs, n_cells, n_qp, dim=2, stream=0):
     """f at the data quadrature points, i.i.d. uniform[-1,1):
     array [nrhs][n_cells][n_qp][dim]."""

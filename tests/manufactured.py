@@ -76,3 +76,42 @@ def cavity_source(X, nu, beta, wind_scale):
     conv = wind_scale * np.einsum("...ij,...j->...i", G, u)
     gp = np.stack([(1 - 2 * x) * (1 - y), -x * (1 - x)], axis=-1)
     return -nu * lap + beta * u + conv + gp
+
+
+# Manufactured 3D solution of Sec. 5.1: with g(t) = t^2 (1-t)^2,
+# u = (g(x) g'(y) g'(z), g(y) g'(x) g'(z), -2 g(z) g'(x) g'(y)) (divergence
+# free, zero on the boundary of the unit cube), p = x(1-x)(1-y)(1-z) - 1/24.
+def velocity3(X):
+    x, y, z = X[..., 0], X[..., 1], X[..., 2]
+    return np.stack([g0(x) * g1(y) * g1(z), g0(y) * g1(x) * g1(z), -2 * g0(z) * g1(x) * g1(y)], axis=-1)
+
+
+def grad_velocity3(X):
+    """[..., i, j] = d u_i / d x_j."""
+    x, y, z = X[..., 0], X[..., 1], X[..., 2]
+    G = np.zeros(X.shape[:-1] + (3, 3))
+    G[..., 0, 0] = g1(x) * g1(y) * g1(z)
+    G[..., 0, 1] = g0(x) * g2(y) * g1(z)
+    G[..., 0, 2] = g0(x) * g1(y) * g2(z)
+    G[..., 1, 0] = g0(y) * g2(x) * g1(z)
+    G[..., 1, 1] = g1(y) * g1(x) * g1(z)
+    G[..., 1, 2] = g0(y) * g1(x) * g2(z)
+    G[..., 2, 0] = -2 * g0(z) * g2(x) * g1(y)
+    G[..., 2, 1] = -2 * g0(z) * g1(x) * g2(y)
+    G[..., 2, 2] = -2 * g1(z) * g1(x) * g1(y)
+    return G
+
+
+def pressure3(X):
+    x, y, z = X[..., 0], X[..., 1], X[..., 2]
+    return x * (1 - x) * (1 - y) * (1 - z) - 1.0 / 24.0
+
+
+def source3(X, nu, beta):
+    x, y, z = X[..., 0], X[..., 1], X[..., 2]
+    lap = np.stack([
+        g2(x) * g1(y) * g1(z) + g0(x) * g3(y) * g1(z) + g0(x) * g1(y) * g3(z),
+        g3(x) * g0(y) * g1(z) + g1(x) * g2(y) * g1(z) + g1(x) * g0(y) * g3(z),
+        -2 * (g3(x) * g1(y) * g0(z) + g1(x) * g3(y) * g0(z) + g1(x) * g1(y) * g2(z))], axis=-1)
+    gp = np.stack([(1 - 2 * x) * (1 - y) * (1 - z), -x * (1 - x) * (1 - z), -x * (1 - x) * (1 - y)], axis=-1)
+    return -nu * lap + beta * velocity3(X) + gp

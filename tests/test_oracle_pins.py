@@ -412,3 +412,24 @@ def test_postprocessing_keeps_the_mean_and_matches_the_lifting():
         lhs = np.einsum("q,qij,qrj->ir", w, gu, qg)
         rhs = np.einsum("q,qij,qrj->ir", w, -L / 0.7, qg)
         assert np.abs(lhs - rhs).max() <= 1e-6 * np.abs(rhs).max()
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_hp_multigrid_robust_k_ge_1(k):
+    """Thm 3.2 (soft) for k >= 1: MG_hp-preconditioned CG counts stay below
+    26 over levels 2-4 (4x4 .. 16x16 squares from 2x2) for eps^-1 = 1 and
+    1e4, and their growth from level to level does not accelerate (at most
+    5, and no larger than the previous step).  Planted in the oracle, a
+    mode-0 injection on the wrong mode gives up to 200 iterations, a patch
+    missing one facet 200, and the transfer without the harmonic extension
+    56 and 129 at eps^-1 = 1e4, so each fails this pin."""
+    for gamma in (1.0, 1e4):
+        its = []
+        for n_refine in (1, 2, 3):
+            c, t = synth.kuhn_square(2)
+            S = solver.Setup(c, t, n_refine, k, 1.0, 1.0, gamma)
+            b = synth.uniform_pm1(0, 5, (S.Aeps.shape[0],))
+            its.append(S.inner(b, max_it=200)[1])
+        assert max(its) <= 26, (gamma, its)
+        assert its[2] - its[1] <= 5 and its[2] - its[1] <= its[1] - its[0] + 1, (gamma, its)
