@@ -362,6 +362,21 @@ hdgmg_status hdgmg_precondition(hdgmg_ctx* ctx, const double* r, double* z);
 hdgmg_status hdgmg_inner_solve(hdgmg_ctx* ctx, const double* b, double* x,
                                int* its, double* rel_res);
 
+/* hdgmg_inner_solve for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same solve, kernels and arguments, but the Krylov
+ * solvers' scalars and reduction partials live in a fixed file-scope device
+ * array of the library (36,000 FP64 words = 288,000 bytes per GPU, held until
+ * the process ends) instead of the context's workspace.  The call allocates
+ * nothing (no hipMalloc / hipFree, no allocator callback); the context's
+ * vectors, operators and preconditioner are those hdgmg_setup and
+ * hdgmg_assemble allocated.  Every call on one GPU shares that array and
+ * clears it first: calls that overlap on one GPU (contexts on different
+ * streams or threads) race and must be serialised by the caller.  Limit:
+ * FGMRES restart <= 64 (EINVAL beyond).  Results equal hdgmg_inner_solve's. */
+hdgmg_status hdgmg_inner_solve_noalloc(hdgmg_ctx* ctx, const double* b, double* x,
+                                       int* its, double* rel_res);
+
 /* Local recovery (Sec. 3.2): from state [N_skel + n_cells] (device) and
  * f_qp (device) compute u_qp and p_qp (device) at the data points.  The
  * pressure is returned as stored (the Uzawa iteration keeps it mean-free). */

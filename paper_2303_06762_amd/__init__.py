@@ -85,7 +85,7 @@ SYMBOLS = ["hdgmg_default_opts", "hdgmg_setup", "hdgmg_assemble", "hdgmg_solve",
            "hdgmg_solve_adjoint", "hdgmg_solve_x0", "hdgmg_set_wind", "hdgmg_set_newton", "hdgmg_set_dirichlet", "hdgmg_postprocess",
            "hdgmg_solve_batch", "hdgmg_solve_adjoint_batch",
            "hdgmg_rhs",
-           "hdgmg_apply", "hdgmg_precondition", "hdgmg_inner_solve", "hdgmg_recover",
+           "hdgmg_apply", "hdgmg_precondition", "hdgmg_inner_solve", "hdgmg_inner_solve_noalloc", "hdgmg_recover",
            "hdgmg_query", "hdgmg_export", "hdgmg_kernel_timer", "hdgmg_kernel_timer_read",
            "hdgmg_last_error", "hdgmg_destroy"]
 
@@ -118,8 +118,9 @@ def lib():
     for name in ("hdgmg_rhs", "hdgmg_apply", "hdgmg_precondition"):
         getattr(L, name).argtypes = [vp, vp, vp]
         getattr(L, name).restype = i32
-    L.hdgmg_inner_solve.argtypes = [vp, vp, vp, ctypes.POINTER(i32), ctypes.POINTER(dbl)]
-    L.hdgmg_inner_solve.restype = i32
+    for name in ("hdgmg_inner_solve", "hdgmg_inner_solve_noalloc"):
+        getattr(L, name).argtypes = [vp, vp, vp, ctypes.POINTER(i32), ctypes.POINTER(dbl)]
+        getattr(L, name).restype = i32
     L.hdgmg_solve_batch.argtypes = [ctypes.POINTER(vp), i32, i32, vp, vp, vp, vp, ctypes.POINTER(Info)]
     L.hdgmg_solve_batch.restype = i32
     L.hdgmg_solve_adjoint_batch.argtypes = [ctypes.POINTER(vp), i32, i32, vp, vp, vp, vp, vp,
@@ -256,6 +257,14 @@ class Solver:
         its, rel = ctypes.c_int(), ctypes.c_double()
         st = self._check(lib().hdgmg_inner_solve(self._h, _ptr(b), _ptr(x), ctypes.byref(its),
                                                  ctypes.byref(rel)), allow=(0, 1))
+        return x, its.value, rel.value, st
+
+    def inner_solve_noalloc(self, b, x):
+        """inner_solve into the caller's x with the library's fixed device
+        scratch (no allocation during the call)."""
+        its, rel = ctypes.c_int(), ctypes.c_double()
+        st = self._check(lib().hdgmg_inner_solve_noalloc(self._h, _ptr(b), _ptr(x), ctypes.byref(its),
+                                                         ctypes.byref(rel)), allow=(0, 1))
         return x, its.value, rel.value, st
 
     def recover(self, f_qp, state):

@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -28,9 +29,27 @@
 
 using namespace hdgmg;
 
+// See g_scratch_dev: the no-allocation inner solve's Krylov scratch.
+static __device__ __align__(256) double scratch[36000];
+
+
 namespace {
 
 std::string g_setup_error;
+
+// Fixed device scratch of hdgmg_inner_solve_noalloc: the Krylov solvers'
+// scalars and reduction partials (KrylovScratch below) in one file-scope
+// array, so that the call needs no allocation.  Each GPU holds its own copy
+// until the process ends; its address on a device is looked up once, with
+// that device current (hipGetSymbolAddress), and only that address is used
+// from host code.  Layout in words: sc [0, 32), part [32, 32 + 4 RED_BLOCKS),
+// gm_part (65 RED_BLOCKS: restart <= 64), gm_h (512), gm_y (128).
+constexpr long NA_SC = 0, NA_PART = 32, NA_GMPART = NA_PART + 4 * RED_BLOCKS,
+               NA_GMH = NA_GMPART + 65 * RED_BLOCKS, NA_GMY = NA_GMH + 512, NA_WORDS = NA_GMY + 128;
+constexpr int NA_MAX_DEVICES = 64;
+static_assert(NA_WORDS == 36000, "scratch layout must fill the array");
+double* g_scratch_dev[NA_MAX_DEVICES] = {};
+std::mutex g_scratch_mu;
 
 struct DevLevel {
   int nc = 0, nint = 0, m = 1, nK = 6;
@@ -194,6 +213,7 @@ struct hdgmg_ctx {
   double *x = nullptr, *r = nullptr, *r_old = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
   double *b = nullptr, *gvec = nullptr, *lam = nullptr, *p0 = nullptr;
   double *sc = nullptr, *part = nullptr;
+  int dev = 0;  // device current at hdgmg_setup (the stream's device)
   double *fdiv = nullptr, *cdiv = nullptr, *area = nullptr;
   double* gK = nullptr;
   double* statebuf = nullptr;  // [N_skel + n_cells] for hdgmg_solve without state
@@ -786,17 +806,32 @@ void mg_hp_body(hdgmg_ctx* ctx, const double* r, double* z) {
   for (int s = 0; s < ctx->opts.m_relax; ++s) sweep(ctx, KL, z, r, false, -1);
 }
 
+// Device scratch of the Krylov solvers: the recurrence scalars (sc, SC_N
+// words), block partials of the dot products (part, 4 RED_BLOCKS words) and,
+// for FGMRES, the partials of the projections on the basis (gm_part,
+// (restart+1) RED_BLOCKS words), the projection coefficients of both
+// Gram-Schmidt passes plus the new norm (gm_h, 4*128 words) and the
+// least-squares solution (gm_y, 128 words).  Every word is written before it
+// is read within one solve.
+struct KrylovScratch {
+  double *sc, *part, *gm_part, *gm_h, *gm_y;
+};
+KrylovScratch ctx_scratch(const hdgmg_ctx* ctx) {
+  return KrylovScratch{ctx->sc, ctx->part, ctx->gm_part, ctx->gm_h, ctx->gm_y};
+}
+
 // Flexible CG for A^eps x = b from x = 0.
-hdgmg_status fcg(hdgmg_ctx* ctx, const double* b, double* x, int* its_out, double* rel_out) {
+hdgmg_status fcg(hdgmg_ctx* ctx, const KrylovScratch& W, const double* b, double* x, int* its_out,
+                 double* rel_out) {
   const long n = ctx->K.ndof;
   const int NB = RED_BLOCKS;
   hipStream_t st = ctx->st;
   double hs[SC_N];
   launch_fill(st, n, 0.0, x);
   launch_copy(st, n, b, ctx->r);
-  launch_dot(st, n, ctx->r, ctx->r, ctx->part, NB);
-  launch_finalize(st, ctx->part, NB, 1, ctx->sc, SC_BB);
-  HIPC(hipMemcpyAsync(hs, ctx->sc, sizeof(hs), hipMemcpyDeviceToHost, st));
+  launch_dot(st, n, ctx->r, ctx->r, W.part, NB);
+  launch_finalize(st, W.part, NB, 1, W.sc, SC_BB);
+  HIPC(hipMemcpyAsync(hs, W.sc, sizeof(hs), hipMemcpyDeviceToHost, st));
   HIPC(hipStreamSynchronize(st));
   const double r0 = std::sqrt(hs[SC_BB]);
   if (!std::isfinite(r0)) {
@@ -808,18 +843,18 @@ hdgmg_status fcg(hdgmg_ctx* ctx, const double* b, double* x, int* its_out, doubl
   if (rel_out) *rel_out = r0 > 0 ? 1.0 : 0.0;
   if (r0 <= tol) return HDGMG_OK;
   mg_hp(ctx, ctx->r, ctx->z);
-  launch_dot(st, n, ctx->z, ctx->r, ctx->part, NB);
-  launch_finalize(st, ctx->part, NB, 1, ctx->sc, SC_ZR);
+  launch_dot(st, n, ctx->z, ctx->r, W.part, NB);
+  launch_finalize(st, W.part, NB, 1, W.sc, SC_ZR);
   launch_copy(st, n, ctx->z, ctx->p);
   int it = 0;
   double rn = r0;
   while (it < ctx->opts.max_it) {
     apply_k(ctx, ctx->p, ctx->q, 1.0, nullptr);
-    launch_dot(st, n, ctx->p, ctx->q, ctx->part, NB);
-    launch_finalize(st, ctx->part, NB, 1, ctx->sc, SC_PQ);
-    launch_fcg_xr(st, n, x, ctx->r, ctx->r_old, ctx->p, ctx->q, ctx->sc, ctx->part, NB);
-    launch_finalize(st, ctx->part, NB, 1, ctx->sc, SC_RR);
-    HIPC(hipMemcpyAsync(hs, ctx->sc, sizeof(hs), hipMemcpyDeviceToHost, st));
+    launch_dot(st, n, ctx->p, ctx->q, W.part, NB);
+    launch_finalize(st, W.part, NB, 1, W.sc, SC_PQ);
+    launch_fcg_xr(st, n, x, ctx->r, ctx->r_old, ctx->p, ctx->q, W.sc, W.part, NB);
+    launch_finalize(st, W.part, NB, 1, W.sc, SC_RR);
+    HIPC(hipMemcpyAsync(hs, W.sc, sizeof(hs), hipMemcpyDeviceToHost, st));
     HIPC(hipStreamSynchronize(st));
     ++it;
     if (!std::isfinite(hs[SC_RR]) || !std::isfinite(hs[SC_PQ]) || !std::isfinite(hs[SC_ZR])) {
@@ -835,10 +870,10 @@ hdgmg_status fcg(hdgmg_ctx* ctx, const double* b, double* x, int* its_out, doubl
     if (rel_out) *rel_out = rn / r0;
     if (rn <= tol) return HDGMG_OK;
     mg_hp(ctx, ctx->r, ctx->z);
-    launch_dot2(st, n, ctx->z, ctx->r, ctx->r_old, ctx->part, NB);
-    launch_finalize(st, ctx->part, NB, 2, ctx->sc, SC_ZRN);
-    launch_fcg_p(st, n, ctx->p, ctx->z, ctx->sc);
-    launch_scalar_move(st, ctx->sc, SC_ZRN, SC_ZR);
+    launch_dot2(st, n, ctx->z, ctx->r, ctx->r_old, W.part, NB);
+    launch_finalize(st, W.part, NB, 2, W.sc, SC_ZRN);
+    launch_fcg_p(st, n, ctx->p, ctx->z, W.sc);
+    launch_scalar_move(st, W.sc, SC_ZRN, SC_ZR);
   }
   ctx->err = "inner solve reached max_it";
   return HDGMG_NOT_CONVERGED;
@@ -850,7 +885,8 @@ hdgmg_status fcg(hdgmg_ctx* ctx, const double* b, double* x, int* its_out, doubl
 // Gram-Schmidt in exact arithmetic).  The Hessenberg least-squares problem
 // (Givens rotations) is solved on the host, one transfer of the new column
 // per iteration.  Stops at |residual estimate| <= max(rtol ||r_0||, atol).
-hdgmg_status fgmres(hdgmg_ctx* ctx, const double* b, double* x, int* its_out, double* rel_out) {
+hdgmg_status fgmres(hdgmg_ctx* ctx, const KrylovScratch& W, const double* b, double* x, int* its_out,
+                    double* rel_out) {
   const long n = ctx->K.ndof;
   const int m = ctx->opts.restart, NB = RED_BLOCKS;
   hipStream_t st = ctx->st;
@@ -859,10 +895,10 @@ hdgmg_status fgmres(hdgmg_ctx* ctx, const double* b, double* x, int* its_out, do
   auto Vj = [&](int j) { return V + (long)j * n; };
   auto Zj = [&](int j) { return Z + (long)j * n; };
   auto norm_of = [&](const double* v, double* out) -> hdgmg_status {
-    launch_dot(st, n, v, v, ctx->part, NB);
-    launch_finalize(st, ctx->part, NB, 1, ctx->sc, SC_BB);
+    launch_dot(st, n, v, v, W.part, NB);
+    launch_finalize(st, W.part, NB, 1, W.sc, SC_BB);
     double hs[SC_N];
-    HIPC(hipMemcpyAsync(hs, ctx->sc, sizeof(hs), hipMemcpyDeviceToHost, st));
+    HIPC(hipMemcpyAsync(hs, W.sc, sizeof(hs), hipMemcpyDeviceToHost, st));
     HIPC(hipStreamSynchronize(st));
     *out = std::sqrt(hs[SC_BB]);
     return HDGMG_OK;
@@ -895,14 +931,14 @@ hdgmg_status fgmres(hdgmg_ctx* ctx, const double* b, double* x, int* its_out, do
       double* w = Vj(j + 1);
       apply_k(ctx, Zj(j), w, 1.0, nullptr);
       for (int pass = 0; pass < 2; ++pass) {
-        launch_mdot(st, n, j + 1, V, n, w, ctx->gm_part, NB);
-        launch_finalize(st, ctx->gm_part, NB, j + 1, ctx->gm_h + 128 * pass, 0);
-        launch_maxpy(st, n, j + 1, V, n, ctx->gm_h + 128 * pass, -1.0, w);
+        launch_mdot(st, n, j + 1, V, n, w, W.gm_part, NB);
+        launch_finalize(st, W.gm_part, NB, j + 1, W.gm_h + 128 * pass, 0);
+        launch_maxpy(st, n, j + 1, V, n, W.gm_h + 128 * pass, -1.0, w);
       }
-      launch_dot(st, n, w, w, ctx->part, NB);
-      launch_finalize(st, ctx->part, NB, 1, ctx->gm_h + 256, 0);
+      launch_dot(st, n, w, w, W.part, NB);
+      launch_finalize(st, W.part, NB, 1, W.gm_h + 256, 0);
       HIPC(hipGetLastError());
-      HIPC(hipMemcpyAsync(hb.data(), ctx->gm_h, hb.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPC(hipMemcpyAsync(hb.data(), W.gm_h, hb.size() * sizeof(double), hipMemcpyDeviceToHost, st));
       HIPC(hipStreamSynchronize(st));
       for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hb[i] + hb[128 + i];
       const double hn = std::sqrt(std::max(hb[256], 0.0));
@@ -938,8 +974,8 @@ hdgmg_status fgmres(hdgmg_ctx* ctx, const double* b, double* x, int* its_out, do
       for (int q = i + 1; q < jend; ++q) t -= H[(size_t)i * m + q] * y[q];
       y[i] = t / H[(size_t)i * m + i];
     }
-    HIPC(hipMemcpyAsync(ctx->gm_y, y.data(), jend * sizeof(double), hipMemcpyHostToDevice, st));
-    launch_maxpy(st, n, jend, Z, n, ctx->gm_y, 1.0, x);
+    HIPC(hipMemcpyAsync(W.gm_y, y.data(), jend * sizeof(double), hipMemcpyHostToDevice, st));
+    launch_maxpy(st, n, jend, Z, n, W.gm_y, 1.0, x);
     HIPC(hipStreamSynchronize(st));  // y is read before it goes out of scope
     if (its_out) *its_out = its;
     if (rel_out) *rel_out = res / beta0;
@@ -1724,6 +1760,29 @@ hdgmg_status hdgmg_setup(const hdgmg_mesh* mesh, int k, double beta, const doubl
     }
     ctx->st = ctx->own;
   }
+  // address of the no-allocation scratch on this device (once per device)
+  {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NA_MAX_DEVICES) {
+      g_setup_error = "hipGetDevice failed or device index out of range";
+      if (ctx->own) (void)hipStreamDestroy(ctx->own);
+      delete ctx;
+      return HDGMG_EHIP;
+    }
+    ctx->dev = dev;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+      void* ptr = nullptr;
+      hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !ptr) {
+        g_setup_error = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+        if (ctx->own) (void)hipStreamDestroy(ctx->own);
+        delete ctx;
+        return HDGMG_EHIP;
+      }
+      g_scratch_dev[dev] = static_cast<double*>(ptr);
+    }
+  }
   ctx->J = mesh->n_refine + 1;
   ctx->lv.resize(ctx->J);
   Level& L0 = ctx->lv[0];
@@ -1969,9 +2028,43 @@ hdgmg_status hdgmg_inner_solve(hdgmg_ctx* ctx, const double* b, double* x, int* 
   hdgmg_status s;
   if (ctx->opts.oseen) {
     launch_fill(ctx->st, ctx->K.ndof, 0.0, x);
-    s = fgmres(ctx, b, x, its, rel_res);
+    s = fgmres(ctx, ctx_scratch(ctx), b, x, its, rel_res);
   } else {
-    s = fcg(ctx, b, x, its, rel_res);
+    s = fcg(ctx, ctx_scratch(ctx), b, x, its, rel_res);
+  }
+  HIPC(hipStreamSynchronize(ctx->st));
+  return s;
+}
+
+hdgmg_status hdgmg_inner_solve_noalloc(hdgmg_ctx* ctx, const double* b, double* x, int* its,
+                                       double* rel_res) {
+  if (!ctx || !b || !x) return HDGMG_EINVAL;
+  if (!ctx->assembled) {
+    ctx->err = "hdgmg_inner_solve_noalloc before hdgmg_assemble";
+    return HDGMG_ESTATE;
+  }
+  if ((long)(ctx->opts.restart + 1) * RED_BLOCKS > NA_GMH - NA_GMPART) {
+    ctx->err = "hdgmg_inner_solve_noalloc: restart exceeds the fixed scratch (at most 64)";
+    return HDGMG_EINVAL;
+  }
+  double* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    base = g_scratch_dev[ctx->dev];
+  }
+  if (!base) {
+    ctx->err = "hdgmg_inner_solve_noalloc: no scratch address for the context's device";
+    return HDGMG_ESTATE;
+  }
+  const KrylovScratch W{base + NA_SC, base + NA_PART, base + NA_GMPART, base + NA_GMH, base + NA_GMY};
+  // the array keeps the previous call's contents: start from zeros
+  launch_fill(ctx->st, NA_WORDS, 0.0, base);
+  hdgmg_status s;
+  if (ctx->opts.oseen) {
+    launch_fill(ctx->st, ctx->K.ndof, 0.0, x);
+    s = fgmres(ctx, W, b, x, its, rel_res);
+  } else {
+    s = fcg(ctx, W, b, x, its, rel_res);
   }
   HIPC(hipStreamSynchronize(ctx->st));
   return s;
@@ -2142,8 +2235,8 @@ hdgmg_status hdgmg_solve_x0(hdgmg_ctx* ctx, const double* f_qp, const double* x0
     int its = 0;
     double rel = 0.0;
     // Oseen: FGMRES from the latest iterate; Stokes: flexible CG from zero
-    hdgmg_status s = ctx->opts.oseen ? fgmres(ctx, ctx->b, ctx->lam, &its, &rel)
-                                     : fcg(ctx, ctx->b, ctx->lam, &its, &rel);
+    hdgmg_status s = ctx->opts.oseen ? fgmres(ctx, ctx_scratch(ctx), ctx->b, ctx->lam, &its, &rel)
+                                     : fcg(ctx, ctx_scratch(ctx), ctx->b, ctx->lam, &its, &rel);
     if (s < 0) return s;
     if (s == HDGMG_NOT_CONVERGED) result = s;
     launch_uzawa_update(st, KL.nc, KL.m, KL.cell_dofs, ctx->cdiv, ctx->area, ctx->lam, ctx->gamma, ctx->p0,
