@@ -373,7 +373,8 @@ hdgmg_status hdgmg_inner_solve(hdgmg_ctx* ctx, const double* b, double* x,
  * hdgmg_assemble allocated.  Every call on one GPU shares that array and
  * clears it first: calls that overlap on one GPU (contexts on different
  * streams or threads) race and must be serialised by the caller.  Limit:
- * FGMRES restart <= 64 (EINVAL beyond).  Results equal hdgmg_inner_solve's. */
+ * FGMRES restart <= 64 (EINVAL beyond).  Results equal hdgmg_inner_solve's.
+ * Triangular meshes only (ESTATE on a tetrahedral context). */
 hdgmg_status hdgmg_inner_solve_noalloc(hdgmg_ctx* ctx, const double* b, double* x,
                                        int* its, double* rel_res);
 

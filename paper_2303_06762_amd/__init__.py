@@ -172,7 +172,8 @@ class Solver:
         cells = np.ascontiguousarray(cells, dtype=np.int32)
         nu = np.ascontiguousarray(np.atleast_1d(np.asarray(nu, dtype=np.float64)))
         self._keep = (coords, cells, nu)
-        m = Mesh(2, len(coords), coords.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+        self.dim = int(coords.shape[1])
+        m = Mesh(self.dim, len(coords), coords.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                  len(cells), cells.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), int(n_refine))
         if opts is None:
             opts = default_opts(**kw)
@@ -268,7 +269,7 @@ class Solver:
         return x, its.value, rel.value, st
 
     def recover(self, f_qp, state):
-        u = self.torch.empty((self.n_cells, self.n_q, 2), dtype=self.torch.float64, device="cuda")
+        u = self.torch.empty((self.n_cells, self.n_q, self.dim), dtype=self.torch.float64, device="cuda")
         p = self.torch.empty((self.n_cells, self.n_q), dtype=self.torch.float64, device="cuda")
         self._check(lib().hdgmg_recover(self._h, _ptr(f_qp), _ptr(state), _ptr(u), _ptr(p)))
         return u, p
@@ -278,7 +279,7 @@ class Solver:
         skeleton iterate (N_skel), e.g. state[:n_skel] of a previous solve;
         p_init: initial P0 pressure of the AL-Uzawa loop (n_cells), e.g.
         state[n_skel:] of the previous state for a Newton step."""
-        u = self.torch.empty((self.n_cells, self.n_q, 2), dtype=self.torch.float64, device="cuda")
+        u = self.torch.empty((self.n_cells, self.n_q, self.dim), dtype=self.torch.float64, device="cuda")
         p = self.torch.empty((self.n_cells, self.n_q), dtype=self.torch.float64, device="cuda")
         state = self._vec(self.n_skel + self.n_cells)
         info = Info()
@@ -296,7 +297,7 @@ class Solver:
         adj_state, info dict, status); gnu (n_cells) is accumulated into
         when given, else a new zeroed tensor."""
         t = self.torch
-        gf = t.empty((self.n_cells, self.n_q, 2), dtype=t.float64, device="cuda")
+        gf = t.empty((self.n_cells, self.n_q, self.dim), dtype=t.float64, device="cuda")
         if gnu is None:
             gnu = t.zeros(self.n_cells, dtype=t.float64, device="cuda")
         if adj_state is None:
@@ -317,7 +318,7 @@ class Solver:
 
     def postprocess(self, f_qp, state):
         """u* (stPost) at the data points [n_cells][n_q][2] of a solved state."""
-        out = self.torch.empty((self.n_cells, self.n_q, 2), dtype=self.torch.float64, device="cuda")
+        out = self.torch.empty((self.n_cells, self.n_q, self.dim), dtype=self.torch.float64, device="cuda")
         self._check(lib().hdgmg_postprocess(self._h, _ptr(f_qp), _ptr(state), _ptr(out)))
         return out
 
@@ -370,16 +371,17 @@ class Solver:
         return ms.value, n.value, b.value
 
     def data_points(self):
-        out = self.torch.empty((self.n_cells, self.n_q, 2), dtype=self.torch.float64, device="cuda")
+        out = self.torch.empty((self.n_cells, self.n_q, self.dim), dtype=self.torch.float64, device="cuda")
         self._check(lib().hdgmg_export(self._h, 2, 0, _ptr(out), out.numel() * 8))
         return out
 
     def export(self, what, level=0):
-        if what == 0:
-            nK = 6 * (self.k + 1)
-            out = self.torch.empty((self.n_cells, nK, nK), dtype=self.torch.float64, device="cuda")
+        if self.dim == 3:
+            nK = 6 * (self.k + 1) * (self.k + 2) if what == 0 else 12
         else:
-            out = self.torch.empty((self.query(8, level), 6, 6), dtype=self.torch.float64, device="cuda")
+            nK = 6 * (self.k + 1) if what == 0 else 6
+        n = self.n_cells if what == 0 else self.query(8, level)
+        out = self.torch.empty((n, nK, nK), dtype=self.torch.float64, device="cuda")
         self._check(lib().hdgmg_export(self._h, what, level, _ptr(out), out.numel() * 8))
         return out
 

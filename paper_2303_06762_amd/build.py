@@ -6,7 +6,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhdgmg.so")
-SOURCES = ["solver.hip", "kernels.hip", "coarse.hip", "fast.hip", "condense.hip", "topology.cpp", "host_setup.cpp"]
+SOURCES = ["solver.hip", "kernels.hip", "coarse.hip", "fast.hip", "condense.hip", "topology.cpp", "host_setup.cpp",
+           "mesh3d.cpp", "tet.hip", "solve3d.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          # packed FP32 instructions stay off (see the design notes)
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -26,6 +26,7 @@
 #include "kernels.hpp"
 #include "host_setup.hpp"
 #include "topology.hpp"
+#include "solve3d.hpp"
 
 using namespace hdgmg;
 
@@ -214,6 +215,7 @@ struct hdgmg_ctx {
   double *b = nullptr, *gvec = nullptr, *lam = nullptr, *p0 = nullptr;
   double *sc = nullptr, *part = nullptr;
   int dev = 0;  // device current at hdgmg_setup (the stream's device)
+  Ctx3* d3 = nullptr;  // tetrahedral meshes: the three-dimensional context
   double *fdiv = nullptr, *cdiv = nullptr, *area = nullptr;
   double* gK = nullptr;
   double* statebuf = nullptr;  // [N_skel + n_cells] for hdgmg_solve without state
@@ -1683,11 +1685,17 @@ void hdgmg_default_opts(hdgmg_opts* o) {
 }
 
 const char* hdgmg_last_error(const hdgmg_ctx* ctx) {
+  if (ctx && ctx->d3) return d3_error(ctx->d3);
   return ctx ? ctx->err.c_str() : g_setup_error.c_str();
 }
 
 void hdgmg_destroy(hdgmg_ctx* ctx) {
   if (!ctx) return;
+  if (ctx->d3) {
+    d3_destroy(ctx->d3);
+    delete ctx;
+    return;
+  }
   if (ctx->st) (void)hipStreamSynchronize(ctx->st);
   drop_graph(ctx);
   for (auto& T : ctx->timers) kt_clear(T);
@@ -1710,9 +1718,29 @@ hdgmg_status hdgmg_setup(const hdgmg_mesh* mesh, int k, double beta, const doubl
     g_setup_error = "give both allocator callbacks or neither";
     return HDGMG_EINVAL;
   }
+  if (mesh->dim == 3 && mesh->coords && mesh->cells) {
+    if (!(beta >= 0) || !(gamma > 0)) {
+      g_setup_error = "need beta >= 0, gamma > 0";
+      return HDGMG_EINVAL;
+    }
+    for (int i = 0; i < nu_len; ++i)
+      if (!(nu[i] > 0) || !std::isfinite(nu[i])) {
+        g_setup_error = "nu must be positive and finite";
+        return HDGMG_EINVAL;
+      }
+    Ctx3* c3 = nullptr;
+    hdgmg_status s3 = d3_setup(mesh, k, beta, nu, nu_len, gamma, opts, stream, alloc_fn, free_fn, alloc_ctx, &c3,
+                               g_setup_error);
+    if (s3 != HDGMG_OK) return s3;
+    hdgmg_ctx* ctx = new hdgmg_ctx();
+    ctx->d3 = c3;
+    ctx->k = k;
+    *out = ctx;
+    return HDGMG_OK;
+  }
   if (mesh->dim != 2 || mesh->n_vertices < 3 || mesh->n_cells < 1 || !mesh->coords || !mesh->cells ||
       mesh->n_refine < 0 || mesh->n_refine > 12) {
-    g_setup_error = "mesh must be 2D with >= 1 cell and 0 <= n_refine <= 12";
+    g_setup_error = "mesh must be 2D (or 3D) with >= 1 cell and 0 <= n_refine <= 12";
     return HDGMG_EMESH;
   }
   if (k < 0 || k > KMAX || !(beta >= 0) || !(gamma > 0)) {
@@ -1927,6 +1955,7 @@ hdgmg_status hdgmg_setup(const hdgmg_mesh* mesh, int k, double beta, const doubl
 }
 
 hdgmg_status hdgmg_assemble(hdgmg_ctx* ctx) {
+  if (ctx && ctx->d3) return d3_assemble(ctx->d3);
   if (!ctx) return HDGMG_EINVAL;
   ctx->assembled = false;
   drop_graph(ctx);
@@ -1983,6 +2012,7 @@ hdgmg_status hdgmg_assemble(hdgmg_ctx* ctx) {
 }
 
 hdgmg_status hdgmg_rhs(hdgmg_ctx* ctx, const double* f_qp, double* g) {
+  if (ctx && ctx->d3) return f_qp && g ? d3_rhs(ctx->d3, f_qp, g) : HDGMG_EINVAL;
   if (!ctx || !f_qp || !g) return HDGMG_EINVAL;
   if (!ctx->assembled) {
     ctx->err = "hdgmg_rhs before hdgmg_assemble";
@@ -1996,6 +2026,7 @@ hdgmg_status hdgmg_rhs(hdgmg_ctx* ctx, const double* f_qp, double* g) {
 }
 
 hdgmg_status hdgmg_apply(hdgmg_ctx* ctx, const double* x, double* y) {
+  if (ctx && ctx->d3) return x && y ? d3_apply(ctx->d3, x, y) : HDGMG_EINVAL;
   if (!ctx || !x || !y) return HDGMG_EINVAL;
   if (!ctx->assembled) {
     ctx->err = "hdgmg_apply before hdgmg_assemble";
@@ -2008,6 +2039,7 @@ hdgmg_status hdgmg_apply(hdgmg_ctx* ctx, const double* x, double* y) {
 }
 
 hdgmg_status hdgmg_precondition(hdgmg_ctx* ctx, const double* r, double* z) {
+  if (ctx && ctx->d3) return r && z ? d3_precondition(ctx->d3, r, z) : HDGMG_EINVAL;
   if (!ctx || !r || !z) return HDGMG_EINVAL;
   if (!ctx->assembled) {
     ctx->err = "hdgmg_precondition before hdgmg_assemble";
@@ -2020,6 +2052,7 @@ hdgmg_status hdgmg_precondition(hdgmg_ctx* ctx, const double* r, double* z) {
 }
 
 hdgmg_status hdgmg_inner_solve(hdgmg_ctx* ctx, const double* b, double* x, int* its, double* rel_res) {
+  if (ctx && ctx->d3) return b && x ? d3_inner_solve(ctx->d3, b, x, its, rel_res, nullptr, nullptr) : HDGMG_EINVAL;
   if (!ctx || !b || !x) return HDGMG_EINVAL;
   if (!ctx->assembled) {
     ctx->err = "hdgmg_inner_solve before hdgmg_assemble";
@@ -2039,6 +2072,7 @@ hdgmg_status hdgmg_inner_solve(hdgmg_ctx* ctx, const double* b, double* x, int* 
 hdgmg_status hdgmg_inner_solve_noalloc(hdgmg_ctx* ctx, const double* b, double* x, int* its,
                                        double* rel_res) {
   if (!ctx || !b || !x) return HDGMG_EINVAL;
+  if (ctx->d3) return HDGMG_ESTATE;  // triangular meshes only
   if (!ctx->assembled) {
     ctx->err = "hdgmg_inner_solve_noalloc before hdgmg_assemble";
     return HDGMG_ESTATE;
@@ -2071,6 +2105,9 @@ hdgmg_status hdgmg_inner_solve_noalloc(hdgmg_ctx* ctx, const double* b, double* 
 }
 
 hdgmg_status hdgmg_set_wind(hdgmg_ctx* ctx, const double* w_qp) {
+  if (ctx && ctx->d3) {
+    return HDGMG_ESTATE;
+  }
   if (!ctx) return HDGMG_EINVAL;
   if (!ctx->opts.oseen) {
     ctx->err = "hdgmg_set_wind needs a context set up with opts.oseen = 1";
@@ -2136,6 +2173,9 @@ hdgmg_status hdgmg_set_wind(hdgmg_ctx* ctx, const double* w_qp) {
 }
 
 hdgmg_status hdgmg_set_newton(hdgmg_ctx* ctx, const double* state_prev) {
+  if (ctx && ctx->d3) {
+    return HDGMG_ESTATE;
+  }
   if (!ctx) return HDGMG_EINVAL;
   if (!state_prev) {
     if (ctx->has_newton) {
@@ -2164,6 +2204,9 @@ hdgmg_status hdgmg_set_newton(hdgmg_ctx* ctx, const double* state_prev) {
 }
 
 hdgmg_status hdgmg_set_dirichlet(hdgmg_ctx* ctx, const double* uhat_b) {
+  if (ctx && ctx->d3) {
+    return HDGMG_ESTATE;
+  }
   if (!ctx) return HDGMG_EINVAL;
   ctx->has_bd = false;
   if (!uhat_b) return HDGMG_OK;
@@ -2176,6 +2219,7 @@ hdgmg_status hdgmg_set_dirichlet(hdgmg_ctx* ctx, const double* uhat_b) {
 
 hdgmg_status hdgmg_recover(hdgmg_ctx* ctx, const double* f_qp, const double* state, double* u_qp,
                            double* p_qp) {
+  if (ctx && ctx->d3) return f_qp && state && u_qp && p_qp ? d3_recover(ctx->d3, f_qp, state, u_qp, p_qp) : HDGMG_EINVAL;
   if (!ctx || !f_qp || !state || !u_qp || !p_qp) return HDGMG_EINVAL;
   if (!ctx->assembled) {
     ctx->err = "hdgmg_recover before hdgmg_assemble";
@@ -2188,6 +2232,9 @@ hdgmg_status hdgmg_recover(hdgmg_ctx* ctx, const double* f_qp, const double* sta
 }
 
 hdgmg_status hdgmg_postprocess(hdgmg_ctx* ctx, const double* f_qp, const double* state, double* ustar_qp) {
+  if (ctx && ctx->d3) {
+    return HDGMG_ESTATE;
+  }
   if (!ctx || !f_qp || !state || !ustar_qp) return HDGMG_EINVAL;
   if (!ctx->assembled) {
     ctx->err = "hdgmg_postprocess before hdgmg_assemble";
@@ -2210,6 +2257,11 @@ hdgmg_status hdgmg_solve(hdgmg_ctx* ctx, const double* f_qp, double* u_qp, doubl
 
 hdgmg_status hdgmg_solve_x0(hdgmg_ctx* ctx, const double* f_qp, const double* x0, const double* p_init,
                             double* u_qp, double* p_qp, double* state, hdgmg_info* info) {
+  if (ctx && ctx->d3) {
+    if (!f_qp || !u_qp || !p_qp) return HDGMG_EINVAL;
+    if (x0 || p_init) return HDGMG_EINVAL;
+    return d3_solve(ctx->d3, f_qp, nullptr, u_qp, p_qp, state, info);
+  }
   if (!ctx || !f_qp || !u_qp || !p_qp) return HDGMG_EINVAL;
   if (!ctx->assembled) {
     ctx->err = "hdgmg_solve before hdgmg_assemble";
@@ -2289,6 +2341,9 @@ static hdgmg_status adjoint_buffers(hdgmg_ctx* ctx) {
 
 hdgmg_status hdgmg_solve_adjoint(hdgmg_ctx* ctx, const double* f_qp, const double* state, const double* gu_qp,
                                  double* gf_qp, double* gnu, double* adj_state, hdgmg_info* info) {
+  if (ctx && ctx->d3) {
+    return HDGMG_ESTATE;
+  }
   if (!ctx || !f_qp || !state || !gu_qp || !gf_qp) return HDGMG_EINVAL;
   if (!ctx->assembled) {
     ctx->err = "hdgmg_solve_adjoint before hdgmg_assemble";
@@ -2353,6 +2408,7 @@ hdgmg_status hdgmg_solve_adjoint_batch(hdgmg_ctx* const* ctxs, int nctx, int nrh
 }
 
 hdgmg_status hdgmg_kernel_timer(hdgmg_ctx* ctx, int cls, int enable) {
+  if (ctx && ctx->d3) return d3_kernel_timer(ctx->d3, cls, enable);
   if (!ctx || cls < 0 || cls > 4) return HDGMG_EINVAL;
   HIPC(hipStreamSynchronize(ctx->st));
   kt_clear(ctx->timers[cls]);
@@ -2362,6 +2418,7 @@ hdgmg_status hdgmg_kernel_timer(hdgmg_ctx* ctx, int cls, int enable) {
 
 hdgmg_status hdgmg_kernel_timer_read(hdgmg_ctx* ctx, int cls, double* total_ms, int64_t* launches,
                                      double* bytes) {
+  if (ctx && ctx->d3) return d3_kernel_timer_read(ctx->d3, cls, total_ms, launches, bytes);
   if (!ctx || cls < 0 || cls > 4) return HDGMG_EINVAL;
   HIPC(hipStreamSynchronize(ctx->st));
   auto& T = ctx->timers[cls];
@@ -2378,6 +2435,7 @@ hdgmg_status hdgmg_kernel_timer_read(hdgmg_ctx* ctx, int cls, double* total_ms, 
 }
 
 hdgmg_status hdgmg_query(const hdgmg_ctx* ctx, int what, int level, int64_t* value) {
+  if (ctx && ctx->d3) return value ? d3_query(ctx->d3, what, level, value) : HDGMG_EINVAL;
   if (!ctx || !value) return HDGMG_EINVAL;
   const Level& LF = ctx->lv.back();
   switch (what) {
@@ -2400,6 +2458,7 @@ hdgmg_status hdgmg_query(const hdgmg_ctx* ctx, int what, int level, int64_t* val
 }
 
 hdgmg_status hdgmg_export(const hdgmg_ctx* cctx, int what, int level, void* dst, size_t bytes) {
+  if (cctx && cctx->d3) return dst ? d3_export(cctx->d3, what, level, dst, bytes) : HDGMG_EINVAL;
   hdgmg_ctx* ctx = const_cast<hdgmg_ctx*>(cctx);
   if (!ctx || !dst) return HDGMG_EINVAL;
   if (!ctx->assembled && (what == 0 || what == 1)) {

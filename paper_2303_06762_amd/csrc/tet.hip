@@ -1,0 +1,944 @@
+// Kernels of the tetrahedral path (see tet.hpp for the formulation).
+#include "tet.hpp"
+
+#include <algorithm>
+
+namespace hdgmg {
+
+namespace {
+
+constexpr int NT = 256;  // threads of the element and patch workgroups
+
+struct WsLayout {
+  long psq, gsq, xtq, psf, xtf, m, r, h, ka, total;
+  int ldk, nrhs;
+};
+
+HDI WsLayout ws_layout(int k, int mode) {
+  const Dims3 d = dims3(k);
+  const int nq = (k + 2) * (k + 2) * (k + 2), nfq = (k + 2) * (k + 2);
+  WsLayout w;
+  w.nrhs = mode == TET_CONDENSE ? d.nK : 1;
+  w.ldk = d.nkkt + w.nrhs;
+  long o = 0;
+  w.psq = o;
+  o += (long)nq * d.nP;
+  w.gsq = o;
+  o += (long)nq * d.nP * 3;
+  w.xtq = o;
+  o += (long)nq * 3;
+  w.psf = o;
+  o += 4L * nfq * d.nP;
+  w.xtf = o;
+  o += 4L * nfq * 3;
+  w.m = o;
+  o += (long)d.nP * d.nP;
+  w.r = o;
+  long rsz = 9L * d.nP * d.nz;
+  if ((long)d.nK * d.nK > rsz) rsz = (long)d.nK * d.nK;
+  o += rsz;
+  w.h = o;
+  o += (long)d.nz * d.nz;
+  w.ka = o;
+  o += (long)d.nkkt * w.ldk;
+  w.total = (o + 31) / 32 * 32;
+  return w;
+}
+
+// monomials xi^(a,b,c) of degree <= k, ordered by degree d, then c = 0..d,
+// then b = 0..d-c (a = d-b-c); values and reference gradients
+__device__ inline void mono3(int k, const double* xi, double* v, double (*g)[3]) {
+  double p[3][K3MAX + 2];
+  for (int d = 0; d < 3; ++d) {
+    p[d][0] = 1.0;
+    for (int i = 1; i <= k; ++i) p[d][i] = p[d][i - 1] * xi[d];
+  }
+  int s = 0;
+  for (int deg = 0; deg <= k; ++deg)
+    for (int c = 0; c <= deg; ++c)
+      for (int b = 0; b <= deg - c; ++b, ++s) {
+        const int a = deg - b - c;
+        v[s] = p[0][a] * p[1][b] * p[2][c];
+        g[s][0] = a > 0 ? a * p[0][a - 1] * p[1][b] * p[2][c] : 0.0;
+        g[s][1] = b > 0 ? b * p[0][a] * p[1][b - 1] * p[2][c] : 0.0;
+        g[s][2] = c > 0 ? c * p[0][a] * p[1][b] * p[2][c - 1] : 0.0;
+      }
+}
+
+struct Geo {
+  double Xs[4][3];
+  int pos[4];  // sorted position of stored vertex i
+  double J[3][3], Ji[3][3];
+  double vol, h;
+  int rf[4][3];  // sorted positions of the vertices of local face i
+  double n[4][3], t1[4][3], t2[4][3], area[4];
+  int sigma[4];
+  double nu;
+};
+
+__device__ void geometry(const TetCells& E, int cell, Geo& G) {
+  int v[4];
+  for (int i = 0; i < 4; ++i) v[i] = E.cells[4 * cell + i];
+  int ord[4] = {0, 1, 2, 3};
+  for (int i = 1; i < 4; ++i)
+    for (int j = i; j > 0 && v[ord[j]] < v[ord[j - 1]]; --j) {
+      int t = ord[j];
+      ord[j] = ord[j - 1];
+      ord[j - 1] = t;
+    }
+  for (int s = 0; s < 4; ++s) {
+    G.pos[ord[s]] = s;
+    for (int d = 0; d < 3; ++d) G.Xs[s][d] = E.X[3 * v[ord[s]] + d];
+  }
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) G.J[r][c] = G.Xs[c + 1][r] - G.Xs[0][r];
+  const double (*J)[3] = G.J;
+  const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                     J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                     J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+  G.Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
+  G.Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+  G.Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+  G.Ji[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
+  G.Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+  G.Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+  G.Ji[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
+  G.Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+  G.Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+  G.vol = fabs(det) / 6.0;
+  double h2 = 0.0;
+  for (int a = 0; a < 4; ++a)
+    for (int b = a + 1; b < 4; ++b) {
+      double s = 0.0;
+      for (int d = 0; d < 3; ++d) s += (G.Xs[a][d] - G.Xs[b][d]) * (G.Xs[a][d] - G.Xs[b][d]);
+      h2 = fmax(h2, s);
+    }
+  G.h = sqrt(h2);
+  for (int i = 0; i < 4; ++i) {
+    int q = 0;
+    for (int s = 0; s < 4; ++s)
+      if (s != G.pos[i]) G.rf[i][q++] = s;
+    const double* X0 = G.Xs[G.rf[i][0]];
+    const double* X1 = G.Xs[G.rf[i][1]];
+    const double* X2 = G.Xs[G.rf[i][2]];
+    double a[3], b[3], n[3];
+    for (int d = 0; d < 3; ++d) {
+      a[d] = X1[d] - X0[d];
+      b[d] = X2[d] - X0[d];
+    }
+    n[0] = a[1] * b[2] - a[2] * b[1];
+    n[1] = a[2] * b[0] - a[0] * b[2];
+    n[2] = a[0] * b[1] - a[1] * b[0];
+    const double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    const double la = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+    G.area[i] = 0.5 * nn;
+    for (int d = 0; d < 3; ++d) {
+      G.n[i][d] = n[d] / nn;
+      G.t1[i][d] = a[d] / la;
+    }
+    G.t2[i][0] = G.n[i][1] * G.t1[i][2] - G.n[i][2] * G.t1[i][1];
+    G.t2[i][1] = G.n[i][2] * G.t1[i][0] - G.n[i][0] * G.t1[i][2];
+    G.t2[i][2] = G.n[i][0] * G.t1[i][1] - G.n[i][1] * G.t1[i][0];
+    double o = 0.0;
+    const double* Xi = G.Xs[G.pos[i]];
+    for (int d = 0; d < 3; ++d) o += ((X0[d] + X1[d] + X2[d]) / 3.0 - Xi[d]) * G.n[i][d];
+    G.sigma[i] = o > 0 ? 1 : -1;
+  }
+  G.nu = E.nu_per_cell ? E.nu[cell] : E.nu[0];
+}
+
+// reference coordinates of point (s, t) of local face i
+__device__ inline void face_xi(const Geo& G, int i, double s, double t, double* xi) {
+  double e[4][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+  for (int d = 0; d < 3; ++d)
+    xi[d] = e[G.rf[i][0]][d] + s * (e[G.rf[i][1]][d] - e[G.rf[i][0]][d]) +
+            t * (e[G.rf[i][2]][d] - e[G.rf[i][0]][d]);
+}
+
+// Value of RT basis function a at a point with monomial values ps [nP] and
+// scaled position xt = (x - X_s0)/h.
+__device__ inline void rt_val(const Dims3& d, int a, const double* ps, const double* xt, double* u) {
+  if (a < 3 * d.nP) {
+    const int c = a / d.nP, s = a % d.nP;
+    u[0] = u[1] = u[2] = 0.0;
+    u[c] = ps[s];
+  } else {
+    const double m = ps[d.nP - d.ntop + (a - 3 * d.nP)];
+    u[0] = xt[0] * m;
+    u[1] = xt[1] * m;
+    u[2] = xt[2] * m;
+  }
+}
+
+// d u_i / d x_j of basis function a (gs: physical monomial gradients [nP][3])
+__device__ inline double rt_grad(const Dims3& d, double h, int a, int i, int j, const double* ps, const double* gs,
+                                 const double* xt) {
+  if (a < 3 * d.nP) {
+    const int c = a / d.nP, s = a % d.nP;
+    return c == i ? gs[3 * s + j] : 0.0;
+  }
+  const int s = d.nP - d.ntop + (a - 3 * d.nP);
+  return ((i == j ? ps[s] : 0.0) + xt[i] * gs[3 * s + j] * h) / h;
+}
+
+__device__ inline double rt_div(const Dims3& d, double h, int a, const double* ps, const double* gs,
+                                const double* xt) {
+  return rt_grad(d, h, a, 0, 0, ps, gs, xt) + rt_grad(d, h, a, 1, 1, ps, gs, xt) + rt_grad(d, h, a, 2, 2, ps, gs, xt);
+}
+
+__global__ void __launch_bounds__(NT) k_tet_local(TetCells E, int mode, int c0, double* ws, const double* f,
+                                                  const double* lam, const double* p0, double* S, double* gK,
+                                                  double* uo, double* po, int* status) {
+  __shared__ Geo G;
+  __shared__ double fct[160];
+  __shared__ int piv;
+  __shared__ double pinv_s;
+  __shared__ double lamK[12 * MF3MAX];
+  const int cell = c0 + blockIdx.x;
+  const int tid = threadIdx.x;
+  const TetTables& T = *E.T;
+  const int k = E.k;
+  const Dims3 d = dims3(k);
+  const int nq = T.nq, nfq = T.nfq, nP = d.nP, nz = d.nz, na = d.na, mF = d.mF;
+  const WsLayout L = ws_layout(k, mode);
+  double* W = ws + (long)blockIdx.x * L.total;
+  double* PSQ = W + L.psq;
+  double* GSQ = W + L.gsq;
+  double* XTQ = W + L.xtq;
+  double* PSF = W + L.psf;
+  double* XTF = W + L.xtf;
+  double* M = W + L.m;
+  double* R = W + L.r;
+  double* H = W + L.h;
+  double* KA = W + L.ka;
+  const int ldk = L.ldk;
+  if (tid == 0) geometry(E, cell, G);
+  if (mode == TET_RECOVER)
+    for (int i = tid; i < d.nK; i += NT) {
+      const int fc = i / (3 * mF);
+      const int dof = E.cell_dofs[4 * cell + fc];
+      lamK[i] = dof < 0 ? 0.0 : lam[(long)dof * 3 * mF + i % (3 * mF)];
+    }
+  __syncthreads();
+  // basis at the volume and face points
+  for (int q = tid; q < nq + 4 * nfq; q += NT) {
+    double xi[3], v[20], g[20][3];
+    double* ps;
+    double* xt;
+    double* gs = nullptr;
+    if (q < nq) {
+      xi[0] = T.xq[q][0];
+      xi[1] = T.xq[q][1];
+      xi[2] = T.xq[q][2];
+      ps = PSQ + (long)q * nP;
+      gs = GSQ + (long)q * nP * 3;
+      xt = XTQ + 3 * q;
+    } else {
+      const int fl = q - nq, fi = fl / nfq, l = fl % nfq;
+      face_xi(G, fi, T.xf[l][0], T.xf[l][1], xi);
+      ps = PSF + (long)fl * nP;
+      xt = XTF + 3 * fl;
+    }
+    mono3(k, xi, v, g);
+    for (int s = 0; s < nP; ++s) {
+      ps[s] = v[s];
+      if (gs)
+        for (int j = 0; j < 3; ++j)
+          gs[3 * s + j] = G.Ji[0][j] * g[s][0] + G.Ji[1][j] * g[s][1] + G.Ji[2][j] * g[s][2];
+    }
+    for (int r = 0; r < 3; ++r) xt[r] = (G.J[r][0] * xi[0] + G.J[r][1] * xi[1] + G.J[r][2] * xi[2]) / G.h;
+  }
+  __syncthreads();
+  // mass of P^k and the lifting blocks R_ij [9][nP][nz]
+  for (int e = tid; e < nP * nP; e += NT) {
+    const int r = e / nP, s = e % nP;
+    double acc = 0.0;
+    for (int q = 0; q < nq; ++q) acc += T.wq[q] * PSQ[(long)q * nP + r] * PSQ[(long)q * nP + s];
+    M[e] = acc * G.vol;
+  }
+  for (long e = tid; e < 9L * nP * nz; e += NT) {
+    const int ij = (int)(e / ((long)nP * nz)), rem = (int)(e % ((long)nP * nz));
+    const int r = rem / nz, col = rem % nz, i = ij / 3, j = ij % 3;
+    double acc = 0.0;
+    if (col < na) {
+      for (int q = 0; q < nq; ++q)
+        acc += T.wq[q] * PSQ[(long)q * nP + r] *
+               rt_grad(d, G.h, col, i, j, PSQ + (long)q * nP, GSQ + (long)q * nP * 3, XTQ + 3 * q);
+      acc *= G.vol;
+      for (int fc = 0; fc < 4; ++fc) {
+        const double nKj = G.sigma[fc] * G.n[fc][j];
+        for (int cc = 0; cc < 2; ++cc) {
+          const double* t = cc == 0 ? G.t1[fc] : G.t2[fc];
+          const double coef = t[i] * nKj;
+          if (coef == 0.0) continue;
+          double s = 0.0;
+          for (int l = 0; l < nfq; ++l) {
+            const double* ps = PSF + ((long)fc * nfq + l) * nP;
+            double u[3];
+            rt_val(d, col, ps, XTF + 3 * (fc * nfq + l), u);
+            s += T.wf[l] * ps[r] * (u[0] * t[0] + u[1] * t[1] + u[2] * t[2]);
+          }
+          acc -= coef * G.area[fc] * s;
+        }
+      }
+    } else {
+      const int c2 = col - na, fc = c2 / (2 * mF), cc = (c2 / mF) % 2, m = c2 % mF;
+      const double* t = cc == 0 ? G.t1[fc] : G.t2[fc];
+      const double coef = t[i] * G.sigma[fc] * G.n[fc][j];
+      if (coef != 0.0) {
+        double s = 0.0;
+        for (int l = 0; l < nfq; ++l) s += T.wf[l] * PSF[((long)fc * nfq + l) * nP + r] * T.phif[l][m];
+        acc = coef * G.area[fc] * s;
+      }
+    }
+    R[e] = acc;
+  }
+  __syncthreads();
+  // Cholesky of M (one thread; nP <= 20), then G_ij = L^-1 R_ij in place
+  if (tid == 0) {
+    for (int c = 0; c < nP; ++c) {
+      double s = M[c * nP + c];
+      for (int p = 0; p < c; ++p) s -= M[c * nP + p] * M[c * nP + p];
+      if (!(s > 0.0)) {
+        atomicOr(status, 1);
+        s = 1.0;
+      }
+      M[c * nP + c] = sqrt(s);
+      for (int r = c + 1; r < nP; ++r) {
+        double t = M[r * nP + c];
+        for (int p = 0; p < c; ++p) t -= M[r * nP + p] * M[c * nP + p];
+        M[r * nP + c] = t / M[c * nP + c];
+      }
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < 9 * nz; e += NT) {
+    const int ij = e / nz, col = e % nz;
+    double* Rc = R + (long)ij * nP * nz + col;
+    for (int r = 0; r < nP; ++r) {
+      double t = Rc[(long)r * nz];
+      for (int p = 0; p < r; ++p) t -= M[r * nP + p] * Rc[(long)p * nz];
+      Rc[(long)r * nz] = t / M[r * nP + r];
+    }
+  }
+  __syncthreads();
+  // H = nu sum_ij G_ij^T G_ij + beta (u_a, u_b) on the RT block
+  for (long e = tid; e < (long)nz * nz; e += NT) {
+    const int a = (int)(e / nz), b = (int)(e % nz);
+    if (b < a) continue;
+    double acc = 0.0;
+    for (int ij = 0; ij < 9; ++ij) {
+      const double* Gm = R + (long)ij * nP * nz;
+      for (int r = 0; r < nP; ++r) acc += Gm[(long)r * nz + a] * Gm[(long)r * nz + b];
+    }
+    acc *= G.nu;
+    if (a < na && b < na && E.beta != 0.0) {
+      double ms = 0.0;
+      for (int q = 0; q < nq; ++q) {
+        double ua[3], ub[3];
+        rt_val(d, a, PSQ + (long)q * nP, XTQ + 3 * q, ua);
+        rt_val(d, b, PSQ + (long)q * nP, XTQ + 3 * q, ub);
+        ms += T.wq[q] * (ua[0] * ub[0] + ua[1] * ub[1] + ua[2] * ub[2]);
+      }
+      acc += E.beta * G.vol * ms;
+    }
+    H[(long)a * nz + b] = acc;
+    H[(long)b * nz + a] = acc;
+  }
+  __syncthreads();
+  // KKT with its right-hand side columns
+  const int nkkt = d.nkkt;
+  for (long e = tid; e < (long)nkkt * ldk; e += NT) KA[e] = 0.0;
+  __syncthreads();
+  for (long e = tid; e < (long)na * na; e += NT) {
+    const int a = (int)(e / na), b = (int)(e % na);
+    KA[(long)a * ldk + b] = H[(long)a * nz + b];
+  }
+  for (int e = tid; e < d.nN * na; e += NT) {
+    const int row = e / na, a = e % na, fc = row / mF, m = row % mF;
+    double s = 0.0;
+    for (int l = 0; l < nfq; ++l) {
+      double u[3];
+      rt_val(d, a, PSF + ((long)fc * nfq + l) * nP, XTF + 3 * (fc * nfq + l), u);
+      s += T.wf[l] * T.phif[l][m] * (u[0] * G.n[fc][0] + u[1] * G.n[fc][1] + u[2] * G.n[fc][2]);
+    }
+    KA[(long)(na + row) * ldk + a] = s;
+    KA[(long)a * ldk + na + row] = s;
+  }
+  for (int e = tid; e < d.nD * na; e += NT) {
+    const int r = e / na + 1, a = e % na;
+    double mean = 0.0;
+    for (int q = 0; q < nq; ++q) mean += T.wq[q] * PSQ[(long)q * nP + r];
+    double s = 0.0;
+    for (int q = 0; q < nq; ++q)
+      s += T.wq[q] * (PSQ[(long)q * nP + r] - mean) *
+           rt_div(d, G.h, a, PSQ + (long)q * nP, GSQ + (long)q * nP * 3, XTQ + 3 * q);
+    s *= G.vol;
+    KA[(long)(na + d.nN + r - 1) * ldk + a] = s;
+    KA[(long)a * ldk + na + d.nN + r - 1] = s;
+  }
+  if (mode == TET_CONDENSE) {
+    for (int e = tid; e < d.nK * na; e += NT) {
+      const int lam_i = e / na, a = e % na;
+      const int fc = lam_i / (3 * mF), c = (lam_i / mF) % 3, m = lam_i % mF;
+      if (c == 0) {
+        if (a == 0) KA[(long)(na + fc * mF + m) * ldk + nkkt + lam_i] = 1.0;
+      } else {
+        KA[(long)a * ldk + nkkt + lam_i] = -H[(long)a * nz + na + (fc * 2 + c - 1) * mF + m];
+      }
+    }
+  } else {
+    // load F_a = (f, u_a); recovery subtracts H_at c^t and sets c^n
+    for (int a = tid; a < na; a += NT) {
+      double s = 0.0;
+      const double* fq = f + (long)cell * nq * 3;
+      for (int q = 0; q < nq; ++q) {
+        double u[3];
+        rt_val(d, a, PSQ + (long)q * nP, XTQ + 3 * q, u);
+        s += T.wq[q] * (u[0] * fq[3 * q] + u[1] * fq[3 * q + 1] + u[2] * fq[3 * q + 2]);
+      }
+      s *= G.vol;
+      if (mode == TET_RECOVER)
+        for (int fc = 0; fc < 4; ++fc)
+          for (int cc = 0; cc < 2; ++cc)
+            for (int m = 0; m < mF; ++m)
+              s -= H[(long)a * nz + na + (fc * 2 + cc) * mF + m] * lamK[(fc * 3 + 1 + cc) * mF + m];
+      KA[(long)a * ldk + nkkt] = s;
+    }
+    if (mode == TET_RECOVER)
+      for (int e = tid; e < d.nN; e += NT) {
+        const int fc = e / mF, m = e % mF;
+        KA[(long)(na + e) * ldk + nkkt] = lamK[(fc * 3) * mF + m];
+      }
+  }
+  __syncthreads();
+  // Gauss-Jordan elimination with partial pivoting
+  for (int j = 0; j < nkkt; ++j) {
+    if (tid == 0) {
+      int p = j;
+      double best = fabs(KA[(long)j * ldk + j]);
+      for (int i = j + 1; i < nkkt; ++i) {
+        const double v = fabs(KA[(long)i * ldk + j]);
+        if (v > best) {
+          best = v;
+          p = i;
+        }
+      }
+      piv = p;
+      if (!(best > 0.0)) atomicOr(status, 2);
+    }
+    __syncthreads();
+    const int p = piv;
+    if (p != j)
+      for (int c = tid; c < ldk; c += NT) {
+        const double t = KA[(long)j * ldk + c];
+        KA[(long)j * ldk + c] = KA[(long)p * ldk + c];
+        KA[(long)p * ldk + c] = t;
+      }
+    __syncthreads();
+    if (tid == 0) {
+      const double v = KA[(long)j * ldk + j];
+      pinv_s = v != 0.0 ? 1.0 / v : 0.0;
+    }
+    __syncthreads();
+    for (int c = j + tid; c < ldk; c += NT) KA[(long)j * ldk + c] *= pinv_s;
+    for (int i = tid; i < nkkt; i += NT) fct[i] = i == j ? 0.0 : KA[(long)i * ldk + j];
+    __syncthreads();
+    const int w = ldk - j;
+    for (long e = tid; e < (long)nkkt * w; e += NT) {
+      const int i = (int)(e / w), c = j + (int)(e % w);
+      if (i == j) continue;
+      KA[(long)i * ldk + c] -= fct[i] * KA[(long)j * ldk + c];
+    }
+    __syncthreads();
+  }
+  // outputs; X = KA[:, nkkt:]
+  if (mode == TET_CONDENSE) {
+    const int nK = d.nK;
+    double* St = R;  // R is no longer needed
+    for (long e = tid; e < (long)nK * nK; e += NT) {
+      const int rho = (int)(e / nK), lc = (int)(e % nK);
+      const int fr = rho / (3 * mF), cr = (rho / mF) % 3, mr = rho % mF;
+      const int fl = lc / (3 * mF), cl = (lc / mF) % 3, ml = lc % mF;
+      double v = 0.0;
+      if (cr == 0) {
+        v = -KA[(long)(na + fr * mF + mr) * ldk + nkkt + lc];
+      } else {
+        const int tr = na + (fr * 2 + cr - 1) * mF + mr;
+        double s = 0.0;
+        for (int a = 0; a < na; ++a) s += H[(long)a * nz + tr] * KA[(long)a * ldk + nkkt + lc];
+        v = s;
+        if (cl != 0) v += H[(long)tr * nz + na + (fl * 2 + cl - 1) * mF + ml];
+      }
+      if (cr == 0 && mr == 0 && cl == 0 && ml == 0)
+        v += E.eps_inv / G.vol * (G.sigma[fr] * G.area[fr]) * (G.sigma[fl] * G.area[fl]);
+      St[e] = v;
+    }
+    __syncthreads();
+    double* out = S + (long)cell * nK * nK;
+    for (long e = tid; e < (long)nK * nK; e += NT) {
+      const int rho = (int)(e / nK), lc = (int)(e % nK);
+      out[e] = 0.5 * (St[e] + St[(long)lc * nK + rho]);
+    }
+  } else if (mode == TET_LOAD) {
+    for (int rho = tid; rho < d.nK; rho += NT) {
+      const int fr = rho / (3 * mF), cr = (rho / mF) % 3, mr = rho % mF;
+      double v;
+      if (cr == 0) {
+        v = KA[(long)(na + fr * mF + mr) * ldk + nkkt];
+      } else {
+        const int tr = na + (fr * 2 + cr - 1) * mF + mr;
+        double s = 0.0;
+        for (int a = 0; a < na; ++a) s += H[(long)a * nz + tr] * KA[(long)a * ldk + nkkt];
+        v = -s;
+      }
+      gK[(long)cell * d.nK + rho] = v;
+    }
+  } else {
+    const double* fq = f;
+    (void)fq;
+    for (int q = tid; q < nq; q += NT) {
+      double u[3] = {0, 0, 0};
+      for (int a = 0; a < na; ++a) {
+        double ua[3];
+        rt_val(d, a, PSQ + (long)q * nP, XTQ + 3 * q, ua);
+        const double c = KA[(long)a * ldk + nkkt];
+        u[0] += c * ua[0];
+        u[1] += c * ua[1];
+        u[2] += c * ua[2];
+      }
+      for (int dd = 0; dd < 3; ++dd) uo[((long)cell * nq + q) * 3 + dd] = u[dd];
+      double pv = p0[cell];
+      for (int r = 1; r < nP; ++r) {
+        double mean = 0.0;
+        for (int qq = 0; qq < nq; ++qq) mean += T.wq[qq] * PSQ[(long)qq * nP + r];
+        pv -= KA[(long)(na + d.nN + r - 1) * ldk + nkkt] * (PSQ[(long)q * nP + r] - mean);
+      }
+      po[(long)cell * nq + q] = pv;
+    }
+  }
+}
+
+// closed-form lowest-order block of one tetrahedron
+__global__ void k_cr_blocks3(const double* __restrict__ X, const int* __restrict__ cells, int nc,
+                             const double* __restrict__ nu, double beta, double eps_inv, double* A) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  double V[4][3];
+  int vid[4];
+  for (int i = 0; i < 4; ++i) {
+    vid[i] = cells[4 * c + i];
+    for (int dd = 0; dd < 3; ++dd) V[i][dd] = X[3 * vid[i] + dd];
+  }
+  double a[3], b[3], e3[3];
+  for (int dd = 0; dd < 3; ++dd) {
+    a[dd] = V[1][dd] - V[0][dd];
+    b[dd] = V[2][dd] - V[0][dd];
+    e3[dd] = V[3][dd] - V[0][dd];
+  }
+  const double vol = fabs(e3[0] * (a[1] * b[2] - a[2] * b[1]) + e3[1] * (a[2] * b[0] - a[0] * b[2]) +
+                          e3[2] * (a[0] * b[1] - a[1] * b[0])) / 6.0;
+  double fr[4][3][3], q[4], g[4][3];
+  for (int i = 0; i < 4; ++i) {
+    int w[3], n = 0;
+    for (int j = 0; j < 4; ++j)
+      if (j != i) w[n++] = j;
+    // the face's vertices sorted by global index
+    for (int s = 1; s < 3; ++s)
+      for (int t = s; t > 0 && vid[w[t]] < vid[w[t - 1]]; --t) {
+        int tmp = w[t];
+        w[t] = w[t - 1];
+        w[t - 1] = tmp;
+      }
+    double u[3], v[3], nn[3];
+    for (int dd = 0; dd < 3; ++dd) {
+      u[dd] = V[w[1]][dd] - V[w[0]][dd];
+      v[dd] = V[w[2]][dd] - V[w[0]][dd];
+    }
+    nn[0] = u[1] * v[2] - u[2] * v[1];
+    nn[1] = u[2] * v[0] - u[0] * v[2];
+    nn[2] = u[0] * v[1] - u[1] * v[0];
+    const double ln = sqrt(nn[0] * nn[0] + nn[1] * nn[1] + nn[2] * nn[2]);
+    const double lu = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    const double area = 0.5 * ln;
+    for (int dd = 0; dd < 3; ++dd) {
+      fr[i][0][dd] = nn[dd] / ln;
+      fr[i][1][dd] = u[dd] / lu;
+    }
+    fr[i][2][0] = fr[i][0][1] * fr[i][1][2] - fr[i][0][2] * fr[i][1][1];
+    fr[i][2][1] = fr[i][0][2] * fr[i][1][0] - fr[i][0][0] * fr[i][1][2];
+    fr[i][2][2] = fr[i][0][0] * fr[i][1][1] - fr[i][0][1] * fr[i][1][0];
+    double o = 0.0;
+    for (int dd = 0; dd < 3; ++dd) o += ((V[w[0]][dd] + V[w[1]][dd] + V[w[2]][dd]) / 3.0 - V[i][dd]) * fr[i][0][dd];
+    const double sg = o > 0 ? 1.0 : -1.0;
+    q[i] = sg * area;
+    for (int dd = 0; dd < 3; ++dd) g[i][dd] = q[i] * fr[i][0][dd] / vol;  // grad of 1 - 3 lambda_i
+  }
+  // RT0 mass: psi_i = (x - V_i) / (3|K|); int_K (x-a).(x-b) = |K|/20 (sum_v |v|^2
+  // + |s|^2) - |K| (a+b).xbar + |K| a.b with s the vertex sum, xbar = s/4
+  double s[3] = {0, 0, 0}, sv = 0.0;
+  for (int i = 0; i < 4; ++i)
+    for (int dd = 0; dd < 3; ++dd) {
+      s[dd] += V[i][dd];
+      sv += V[i][dd] * V[i][dd];
+    }
+  const double ss = s[0] * s[0] + s[1] * s[1] + s[2] * s[2];
+  double Mrt[4][4];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) {
+      double ab = 0.0, axb = 0.0;
+      for (int dd = 0; dd < 3; ++dd) {
+        ab += V[i][dd] * V[j][dd];
+        axb += (V[i][dd] + V[j][dd]) * s[dd] / 4.0;
+      }
+      Mrt[i][j] = vol * ((sv + ss) / 20.0 - axb + ab) / (9.0 * vol * vol);
+    }
+  const double nuc = nu[c];
+  double* out = A + (long)c * 144;
+  for (int i = 0; i < 4; ++i)
+    for (int aa = 0; aa < 3; ++aa)
+      for (int j = 0; j < 4; ++j)
+        for (int bb = 0; bb < 3; ++bb) {
+          const double ff = fr[i][aa][0] * fr[j][bb][0] + fr[i][aa][1] * fr[j][bb][1] + fr[i][aa][2] * fr[j][bb][2];
+          const double gg = g[i][0] * g[j][0] + g[i][1] * g[j][1] + g[i][2] * g[j][2];
+          double v = nuc * ff * gg * vol;
+          if (aa == 0 && bb == 0) v += beta * q[i] * q[j] * Mrt[i][j] + eps_inv * q[i] * q[j] / vol;
+          out[(3 * i + aa) * 12 + 3 * j + bb] = v;
+        }
+}
+
+template <typename TS>
+__global__ void __launch_bounds__(64) k_cell_apply3(Level3View<TS> L, const double* __restrict__ x,
+                                                    double* __restrict__ yK) {
+  __shared__ double xs[12 * MF3MAX];
+  const int c = blockIdx.x, lane = threadIdx.x, nK = L.nK, m3 = 3 * L.mF;
+  for (int i = lane; i < nK; i += 64) {
+    const int dof = L.cell_dofs[4 * c + i / m3];
+    xs[i] = dof < 0 ? 0.0 : x[(long)dof * m3 + i % m3];
+  }
+  __syncthreads();
+  const TS* Sc = L.S + (long)c * nK * nK;
+  for (int row = lane; row < nK; row += 64) {
+    double acc = 0.0;
+    for (int col = 0; col < nK; ++col) acc += (double)Sc[(long)col * nK + row] * xs[col];
+    yK[(long)c * nK + row] = acc;
+  }
+}
+
+__global__ void k_face_gather3(int nint, int m3, int nK, const int* __restrict__ fcell, const int* __restrict__ floc,
+                               const double* __restrict__ yK, double alpha, const double* __restrict__ b,
+                               double* __restrict__ y) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)nint * m3) return;
+  const int fi = (int)(t / m3), rr = (int)(t % m3);
+  double acc = 0.0;
+  for (int s = 0; s < 2; ++s) acc += yK[(long)fcell[2 * fi + s] * nK + floc[2 * fi + s] * m3 + rr];
+  y[t] = (b ? b[t] : 0.0) + alpha * acc;
+}
+
+constexpr int PMAX_CELLS = 12;  // cells around an edge handled per patch
+constexpr int PMAX_FACES = 12;
+
+__global__ void __launch_bounds__(NT) k_patch_inverse3(Level3View<double> L, const int* __restrict__ pf_ptr,
+                                                       const int* __restrict__ pf, const int* __restrict__ pc_ptr,
+                                                       const int* __restrict__ pc, const long* __restrict__ poff,
+                                                       int p0, int ns_max, double* ws, double* pinv,
+                                                       int* status) {
+  __shared__ int slot[PMAX_CELLS][4];
+  __shared__ int piv;
+  __shared__ double pv;
+  __shared__ double fct[PMAX_FACES * 3 * MF3MAX];
+  const int p = p0 + blockIdx.x, tid = threadIdx.x;
+  const int f0 = pf_ptr[p], nf = pf_ptr[p + 1] - f0, c0 = pc_ptr[p], ncl = pc_ptr[p + 1] - c0;
+  const int m3 = 3 * L.mF, ns = nf * m3, nK = L.nK, w = 2 * ns;
+  double* A = ws + (long)blockIdx.x * ns_max * 2 * ns_max;
+  if (nf > PMAX_FACES || ncl > PMAX_CELLS) {
+    if (tid == 0) atomicOr(status, 4);
+    return;
+  }
+  for (int e = tid; e < ncl * 4; e += NT) {
+    const int ci = e / 4, i = e % 4;
+    const int dof = L.cell_dofs[4 * pc[c0 + ci] + i];
+    int s = -1;
+    for (int q = 0; q < nf; ++q)
+      if (pf[f0 + q] == dof) s = q;
+    slot[ci][i] = dof < 0 ? -1 : s;
+  }
+  for (long e = tid; e < (long)ns * w; e += NT) {
+    const int r = (int)(e / w), c = (int)(e % w);
+    A[e] = c - ns == r ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int ci = 0; ci < ncl; ++ci) {
+    const double* Sc = L.S + (long)pc[c0 + ci] * nK * nK;
+    for (long e = tid; e < (long)nK * nK; e += NT) {
+      const int r = (int)(e / nK), c = (int)(e % nK);
+      const int sr = slot[ci][r / m3], sc = slot[ci][c / m3];
+      if (sr < 0 || sc < 0) continue;
+      A[(long)(sr * m3 + r % m3) * w + sc * m3 + c % m3] += Sc[e];
+    }
+    __syncthreads();
+  }
+  for (int j = 0; j < ns; ++j) {
+    if (tid == 0) {
+      int q = j;
+      double best = fabs(A[(long)j * w + j]);
+      for (int i = j + 1; i < ns; ++i)
+        if (fabs(A[(long)i * w + j]) > best) {
+          best = fabs(A[(long)i * w + j]);
+          q = i;
+        }
+      piv = q;
+      pv = best > 0.0 ? 1.0 : 0.0;
+      if (!(best > 0.0)) atomicOr(status, 2);
+    }
+    __syncthreads();
+    const int q = piv;
+    if (q != j)
+      for (int c = tid; c < w; c += NT) {
+        const double t = A[(long)j * w + c];
+        A[(long)j * w + c] = A[(long)q * w + c];
+        A[(long)q * w + c] = t;
+      }
+    __syncthreads();
+    if (tid == 0) {
+      const double v = A[(long)j * w + j];
+      pv = v != 0.0 ? 1.0 / v : 0.0;
+    }
+    __syncthreads();
+    for (int c = tid; c < w; c += NT) A[(long)j * w + c] *= pv;
+    for (int i = tid; i < ns; i += NT) fct[i] = i == j ? 0.0 : A[(long)i * w + j];
+    __syncthreads();
+    for (long e = tid; e < (long)ns * w; e += NT) {
+      const int i = (int)(e / w), c = (int)(e % w);
+      if (i != j) A[e] -= fct[i] * A[(long)j * w + c];
+    }
+    __syncthreads();
+  }
+  double* out = pinv + poff[p];
+  for (long e = tid; e < (long)ns * ns; e += NT) {
+    const int c = (int)(e / ns), r = (int)(e % ns);
+    out[e] = A[(long)r * w + ns + c];  // column c, row r
+  }
+}
+
+template <typename TS>
+__global__ void __launch_bounds__(NT) k_patch_gs3(Level3View<TS> L, const int* __restrict__ pf_ptr,
+                                                  const int* __restrict__ pf, const int* __restrict__ pc_ptr,
+                                                  const int* __restrict__ pc, const long* __restrict__ poff,
+                                                  const TS* __restrict__ pinv, int p0, double* x,
+                                                  const double* __restrict__ b) {
+  __shared__ int slot[PMAX_CELLS][4];
+  __shared__ double xs[PMAX_CELLS][12 * MF3MAX];
+  __shared__ double res[PMAX_FACES * 3 * MF3MAX];
+  __shared__ double part[2 * PMAX_CELLS * 3 * MF3MAX];
+  __shared__ int ptgt[2 * PMAX_CELLS * 3 * MF3MAX];
+  const int p = p0 + blockIdx.x, tid = threadIdx.x;
+  const int f0 = pf_ptr[p], nf = pf_ptr[p + 1] - f0, c0 = pc_ptr[p], ncl = pc_ptr[p + 1] - c0;
+  const int m3 = 3 * L.mF, ns = nf * m3, nK = L.nK;
+  if (nf > PMAX_FACES || ncl > PMAX_CELLS) return;  // rejected on the host
+  for (int e = tid; e < ncl * 4; e += NT) {
+    const int ci = e / 4, i = e % 4;
+    const int dof = L.cell_dofs[4 * pc[c0 + ci] + i];
+    int s = -1;
+    for (int q = 0; q < nf; ++q)
+      if (pf[f0 + q] == dof) s = q;
+    slot[ci][i] = dof < 0 ? -1 : s;
+  }
+  for (int e = tid; e < ncl * nK; e += NT) {
+    const int ci = e / nK, i = e % nK;
+    const int dof = L.cell_dofs[4 * pc[c0 + ci] + i / m3];
+    xs[ci][i] = dof < 0 ? 0.0 : x[(long)dof * m3 + i % m3];
+  }
+  for (int q = tid; q < ns; q += NT) res[q] = b[(long)pf[f0 + q / m3] * m3 + q % m3];
+  __syncthreads();
+  // rows of S_K x_K on the patch faces of each cell (at most two per cell)
+  const int nitem = ncl * 2 * m3;
+  for (int it = tid; it < nitem; it += NT) {
+    const int ci = it / (2 * m3), which = (it / m3) % 2, rr = it % m3;
+    int i = -1, cnt = 0;
+    for (int q = 0; q < 4; ++q)
+      if (slot[ci][q] >= 0) {
+        if (cnt == which) i = q;
+        ++cnt;
+      }
+    ptgt[it] = -1;
+    if (i < 0) continue;
+    const TS* Sc = L.S + (long)pc[c0 + ci] * nK * nK;
+    const int row = i * m3 + rr;
+    double acc = 0.0;
+    for (int col = 0; col < nK; ++col) acc += (double)Sc[(long)col * nK + row] * xs[ci][col];
+    part[it] = acc;
+    ptgt[it] = slot[ci][i] * m3 + rr;
+  }
+  __syncthreads();
+  for (int q = tid; q < ns; q += NT) {
+    double s = res[q];
+    for (int it = 0; it < nitem; ++it)
+      if (ptgt[it] == q) s -= part[it];
+    res[q] = s;
+  }
+  __syncthreads();
+  const TS* Ai = pinv + poff[p];
+  for (int q = tid; q < ns; q += NT) {
+    double s = 0.0;
+    for (int j = 0; j < ns; ++j) s += (double)Ai[(long)j * ns + q] * res[j];
+    x[(long)pf[f0 + q / m3] * m3 + q % m3] += s;
+  }
+}
+
+__global__ void k_mode0_extract3(int n, int mF, const double* __restrict__ r, double* __restrict__ g0,
+                                 double* __restrict__ zero_out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  g0[t] = r[(long)t * mF];
+  if (zero_out) zero_out[t] = 0.0;
+}
+
+__global__ void k_mode0_add3(int n, int mF, const double* __restrict__ u0, double* __restrict__ x) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  x[(long)t * mF] += u0[t];
+}
+
+__global__ void k_uzawa_rhs3(int nint, int mF, const double* __restrict__ g, const double* __restrict__ fdiv,
+                             const int* __restrict__ fcell, const double* __restrict__ p0, double* b) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int m3 = 3 * mF;
+  if (t >= (long)nint * m3) return;
+  double v = g[t];
+  if (t % m3 == 0) {
+    const int fi = (int)(t / m3);
+    v += fdiv[2 * fi] * p0[fcell[2 * fi]] + fdiv[2 * fi + 1] * p0[fcell[2 * fi + 1]];
+  }
+  b[t] = v;
+}
+
+__global__ void __launch_bounds__(256) k_uzawa_update3(int nc, int mF, const int* __restrict__ cell_dofs,
+                                                       const double* __restrict__ cdiv,
+                                                       const double* __restrict__ vol,
+                                                       const double* __restrict__ lam, double eps_inv, double* p0,
+                                                       double* part) {
+  __shared__ double sh[2][256];
+  double s1 = 0.0, s2 = 0.0;
+  for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += (long)gridDim.x * blockDim.x) {
+    double dv = 0.0;
+    for (int i = 0; i < 4; ++i) {
+      const int dof = cell_dofs[4 * c + i];
+      if (dof >= 0) dv += cdiv[4 * c + i] * lam[(long)dof * 3 * mF];
+    }
+    const double dp = -eps_inv * dv / vol[c];
+    const double pn = p0[c] + dp;
+    p0[c] = pn;
+    s1 += vol[c] * dp * dp;
+    s2 += vol[c] * pn * pn;
+  }
+  sh[0][threadIdx.x] = s1;
+  sh[1][threadIdx.x] = s2;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sh[0][threadIdx.x] += sh[0][threadIdx.x + w];
+      sh[1][threadIdx.x] += sh[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = sh[0][0];
+    part[gridDim.x + blockIdx.x] = sh[1][0];
+  }
+}
+
+__global__ void k_f32_copy(long n, const double* __restrict__ in, float* __restrict__ out) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) out[t] = (float)in[t];
+}
+
+inline int blocks(long n, int tpb) { return (int)((n + tpb - 1) / tpb); }
+
+}  // namespace
+
+long tet_ws_words(int k, int mode) { return ws_layout(k, mode).total; }
+
+void launch_tet_local(hipStream_t st, const TetCells& E, int mode, int c0, int nb, double* ws, const double* f,
+                      const double* lam, const double* p0, double* S, double* gK, double* u, double* p,
+                      int* status) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL(k_tet_local, dim3(nb), dim3(NT), 0, st, E, mode, c0, ws, f, lam, p0, S, gK, u, p, status);
+}
+
+void launch_cr_blocks3(hipStream_t st, const double* X, const int* cells, int nc, const double* nu_cells,
+                       double beta, double eps_inv, double* A) {
+  if (nc <= 0) return;
+  hipLaunchKernelGGL(k_cr_blocks3, dim3(blocks(nc, 128)), dim3(128), 0, st, X, cells, nc, nu_cells, beta, eps_inv,
+                     A);
+}
+
+template <typename TS>
+void launch_cell_apply3(hipStream_t st, Level3View<TS> L, const double* x, double* yK) {
+  if (L.nc <= 0) return;
+  hipLaunchKernelGGL(k_cell_apply3<TS>, dim3(L.nc), dim3(64), 0, st, L, x, yK);
+}
+template void launch_cell_apply3<double>(hipStream_t, Level3View<double>, const double*, double*);
+template void launch_cell_apply3<float>(hipStream_t, Level3View<float>, const double*, double*);
+
+void launch_face_gather3(hipStream_t st, int nint, int mF, int nK, const int* fcell, const int* floc,
+                         const double* yK, double alpha, const double* b, double* y) {
+  const long n = (long)nint * 3 * mF;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_face_gather3, dim3(blocks(n, 256)), dim3(256), 0, st, nint, 3 * mF, nK, fcell, floc, yK,
+                     alpha, b, y);
+}
+
+void launch_patch_inverse3(hipStream_t st, Level3View<double> L, const int* pf_ptr, const int* pf,
+                           const int* pc_ptr, const int* pc, const long* poff, int p0, int np, int ns_max,
+                           double* ws, double* pinv, int* status) {
+  if (np <= 0) return;
+  hipLaunchKernelGGL(k_patch_inverse3, dim3(np), dim3(NT), 0, st, L, pf_ptr, pf, pc_ptr, pc, poff, p0, ns_max, ws,
+                     pinv, status);
+}
+
+template <typename TS>
+void launch_patch_gs3(hipStream_t st, Level3View<TS> L, const int* pf_ptr, const int* pf, const int* pc_ptr,
+                      const int* pc, const long* poff, const TS* pinv, int p0, int p1, double* x,
+                      const double* b) {
+  if (p1 <= p0) return;
+  hipLaunchKernelGGL(k_patch_gs3<TS>, dim3(p1 - p0), dim3(NT), 0, st, L, pf_ptr, pf, pc_ptr, pc, poff, pinv, p0, x,
+                     b);
+}
+template void launch_patch_gs3<double>(hipStream_t, Level3View<double>, const int*, const int*, const int*,
+                                       const int*, const long*, const double*, int, int, double*, const double*);
+template void launch_patch_gs3<float>(hipStream_t, Level3View<float>, const int*, const int*, const int*,
+                                      const int*, const long*, const float*, int, int, double*, const double*);
+
+void launch_mode0_extract3(hipStream_t st, int nint, int mF, const double* r, double* g0, double* zero_out) {
+  const int n = 3 * nint;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_mode0_extract3, dim3(blocks(n, 256)), dim3(256), 0, st, n, mF, r, g0, zero_out);
+}
+
+void launch_mode0_add3(hipStream_t st, int nint, int mF, const double* u0, double* x) {
+  const int n = 3 * nint;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_mode0_add3, dim3(blocks(n, 256)), dim3(256), 0, st, n, mF, u0, x);
+}
+
+void launch_uzawa_rhs3(hipStream_t st, int nint, int mF, const double* g, const double* fdiv, const int* fcell,
+                       const double* p0, double* b) {
+  const long n = (long)nint * 3 * mF;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_uzawa_rhs3, dim3(blocks(n, 256)), dim3(256), 0, st, nint, mF, g, fdiv, fcell, p0, b);
+}
+
+void launch_uzawa_update3(hipStream_t st, int nc, int mF, const int* cell_dofs, const double* cdiv,
+                          const double* vol, const double* lam, double eps_inv, double* p0, double* part, int nb) {
+  hipLaunchKernelGGL(k_uzawa_update3, dim3(nb), dim3(256), 0, st, nc, mF, cell_dofs, cdiv, vol, lam, eps_inv, p0,
+                     part);
+}
+
+void launch_f32_copy(hipStream_t st, long n, const double* in, float* out) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_f32_copy, dim3(blocks(n, 256)), dim3(256), 0, st, n, in, out);
+}
+
+}  // namespace hdgmg
