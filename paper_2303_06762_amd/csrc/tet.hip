@@ -10,7 +10,7 @@ namespace {
 constexpr int NT = 256;  // threads of the element and patch workgroups
 
 struct WsLayout {
-  long psq, gsq, xtq, psf, xtf, m, r, h, ka, total;
+  long psq, gsq, xtq, psf, xtf, uq, dvq, m, r, h, ka, total;
   int ldk, nrhs;
 };
 
@@ -31,6 +31,10 @@ HDI WsLayout ws_layout(int k, int mode) {
   o += 4L * nfq * d.nP;
   w.xtf = o;
   o += 4L * nfq * 3;
+  w.uq = o;
+  o += (long)nq * d.na * 3;
+  w.dvq = o;
+  o += (long)nq * d.na;
   w.m = o;
   o += (long)d.nP * d.nP;
   w.r = o;
@@ -207,6 +211,8 @@ __global__ void __launch_bounds__(NT) k_tet_local(TetCells E, int mode, int c0, 
   double* XTQ = W + L.xtq;
   double* PSF = W + L.psf;
   double* XTF = W + L.xtf;
+  double* UQ = W + L.uq;
+  double* DVQ = W + L.dvq;
   double* M = W + L.m;
   double* R = W + L.r;
   double* H = W + L.h;
@@ -249,6 +255,13 @@ __global__ void __launch_bounds__(NT) k_tet_local(TetCells E, int mode, int c0, 
     for (int r = 0; r < 3; ++r) xt[r] = (G.J[r][0] * xi[0] + G.J[r][1] * xi[1] + G.J[r][2] * xi[2]) / G.h;
   }
   __syncthreads();
+  // RT basis values and divergences at the volume points
+  for (long e = tid; e < (long)nq * na; e += NT) {
+    const int q = (int)(e / na), a = (int)(e % na);
+    rt_val(d, a, PSQ + (long)q * nP, XTQ + 3 * q, UQ + 3 * e);
+    DVQ[e] = rt_div(d, G.h, a, PSQ + (long)q * nP, GSQ + (long)q * nP * 3, XTQ + 3 * q);
+  }
+  __syncthreads();
   // mass of P^k and the lifting blocks R_ij [9][nP][nz]
   for (int e = tid; e < nP * nP; e += NT) {
     const int r = e / nP, s = e % nP;
@@ -256,42 +269,47 @@ __global__ void __launch_bounds__(NT) k_tet_local(TetCells E, int mode, int c0, 
     for (int q = 0; q < nq; ++q) acc += T.wq[q] * PSQ[(long)q * nP + r] * PSQ[(long)q * nP + s];
     M[e] = acc * G.vol;
   }
-  for (long e = tid; e < 9L * nP * nz; e += NT) {
-    const int ij = (int)(e / ((long)nP * nz)), rem = (int)(e % ((long)nP * nz));
-    const int r = rem / nz, col = rem % nz, i = ij / 3, j = ij % 3;
-    double acc = 0.0;
+  // one (r, column) pair per item, all nine (i, j) blocks at once
+  for (int e = tid; e < nP * nz; e += NT) {
+    const int r = e / nz, col = e % nz;
+    double acc[9];
+    for (int ij = 0; ij < 9; ++ij) acc[ij] = 0.0;
     if (col < na) {
-      for (int q = 0; q < nq; ++q)
-        acc += T.wq[q] * PSQ[(long)q * nP + r] *
-               rt_grad(d, G.h, col, i, j, PSQ + (long)q * nP, GSQ + (long)q * nP * 3, XTQ + 3 * q);
-      acc *= G.vol;
+      for (int q = 0; q < nq; ++q) {
+        const double wp = T.wq[q] * PSQ[(long)q * nP + r];
+        const double* ps = PSQ + (long)q * nP;
+        const double* gs = GSQ + (long)q * nP * 3;
+        const double* xt = XTQ + 3 * q;
+        for (int i = 0; i < 3; ++i)
+          for (int j = 0; j < 3; ++j) acc[3 * i + j] += wp * rt_grad(d, G.h, col, i, j, ps, gs, xt);
+      }
+      for (int ij = 0; ij < 9; ++ij) acc[ij] *= G.vol;
       for (int fc = 0; fc < 4; ++fc) {
-        const double nKj = G.sigma[fc] * G.n[fc][j];
-        for (int cc = 0; cc < 2; ++cc) {
-          const double* t = cc == 0 ? G.t1[fc] : G.t2[fc];
-          const double coef = t[i] * nKj;
-          if (coef == 0.0) continue;
-          double s = 0.0;
-          for (int l = 0; l < nfq; ++l) {
-            const double* ps = PSF + ((long)fc * nfq + l) * nP;
-            double u[3];
-            rt_val(d, col, ps, XTF + 3 * (fc * nfq + l), u);
-            s += T.wf[l] * ps[r] * (u[0] * t[0] + u[1] * t[1] + u[2] * t[2]);
-          }
-          acc -= coef * G.area[fc] * s;
+        double s1 = 0.0, s2 = 0.0;
+        for (int l = 0; l < nfq; ++l) {
+          const double* ps = PSF + ((long)fc * nfq + l) * nP;
+          double u[3];
+          rt_val(d, col, ps, XTF + 3 * (fc * nfq + l), u);
+          const double wp = T.wf[l] * ps[r];
+          s1 += wp * (u[0] * G.t1[fc][0] + u[1] * G.t1[fc][1] + u[2] * G.t1[fc][2]);
+          s2 += wp * (u[0] * G.t2[fc][0] + u[1] * G.t2[fc][1] + u[2] * G.t2[fc][2]);
         }
+        s1 *= G.area[fc];
+        s2 *= G.area[fc];
+        for (int i = 0; i < 3; ++i)
+          for (int j = 0; j < 3; ++j)
+            acc[3 * i + j] -= (G.t1[fc][i] * s1 + G.t2[fc][i] * s2) * G.sigma[fc] * G.n[fc][j];
       }
     } else {
       const int c2 = col - na, fc = c2 / (2 * mF), cc = (c2 / mF) % 2, m = c2 % mF;
       const double* t = cc == 0 ? G.t1[fc] : G.t2[fc];
-      const double coef = t[i] * G.sigma[fc] * G.n[fc][j];
-      if (coef != 0.0) {
-        double s = 0.0;
-        for (int l = 0; l < nfq; ++l) s += T.wf[l] * PSF[((long)fc * nfq + l) * nP + r] * T.phif[l][m];
-        acc = coef * G.area[fc] * s;
-      }
+      double sf = 0.0;
+      for (int l = 0; l < nfq; ++l) sf += T.wf[l] * PSF[((long)fc * nfq + l) * nP + r] * T.phif[l][m];
+      sf *= G.area[fc];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) acc[3 * i + j] = t[i] * G.sigma[fc] * G.n[fc][j] * sf;
     }
-    R[e] = acc;
+    for (int ij = 0; ij < 9; ++ij) R[((long)ij * nP + r) * nz + col] = acc[ij];
   }
   __syncthreads();
   // Cholesky of M (one thread; nP <= 20), then G_ij = L^-1 R_ij in place
@@ -335,9 +353,8 @@ __global__ void __launch_bounds__(NT) k_tet_local(TetCells E, int mode, int c0, 
     if (a < na && b < na && E.beta != 0.0) {
       double ms = 0.0;
       for (int q = 0; q < nq; ++q) {
-        double ua[3], ub[3];
-        rt_val(d, a, PSQ + (long)q * nP, XTQ + 3 * q, ua);
-        rt_val(d, b, PSQ + (long)q * nP, XTQ + 3 * q, ub);
+        const double* ua = UQ + 3 * ((long)q * na + a);
+        const double* ub = UQ + 3 * ((long)q * na + b);
         ms += T.wq[q] * (ua[0] * ub[0] + ua[1] * ub[1] + ua[2] * ub[2]);
       }
       acc += E.beta * G.vol * ms;
@@ -370,9 +387,7 @@ __global__ void __launch_bounds__(NT) k_tet_local(TetCells E, int mode, int c0, 
     double mean = 0.0;
     for (int q = 0; q < nq; ++q) mean += T.wq[q] * PSQ[(long)q * nP + r];
     double s = 0.0;
-    for (int q = 0; q < nq; ++q)
-      s += T.wq[q] * (PSQ[(long)q * nP + r] - mean) *
-           rt_div(d, G.h, a, PSQ + (long)q * nP, GSQ + (long)q * nP * 3, XTQ + 3 * q);
+    for (int q = 0; q < nq; ++q) s += T.wq[q] * (PSQ[(long)q * nP + r] - mean) * DVQ[(long)q * na + a];
     s *= G.vol;
     KA[(long)(na + d.nN + r - 1) * ldk + a] = s;
     KA[(long)a * ldk + na + d.nN + r - 1] = s;
@@ -393,8 +408,7 @@ __global__ void __launch_bounds__(NT) k_tet_local(TetCells E, int mode, int c0, 
       double s = 0.0;
       const double* fq = f + (long)cell * nq * 3;
       for (int q = 0; q < nq; ++q) {
-        double u[3];
-        rt_val(d, a, PSQ + (long)q * nP, XTQ + 3 * q, u);
+        const double* u = UQ + 3 * ((long)q * na + a);
         s += T.wq[q] * (u[0] * fq[3 * q] + u[1] * fq[3 * q + 1] + u[2] * fq[3 * q + 2]);
       }
       s *= G.vol;
@@ -500,8 +514,7 @@ __global__ void __launch_bounds__(NT) k_tet_local(TetCells E, int mode, int c0, 
     for (int q = tid; q < nq; q += NT) {
       double u[3] = {0, 0, 0};
       for (int a = 0; a < na; ++a) {
-        double ua[3];
-        rt_val(d, a, PSQ + (long)q * nP, XTQ + 3 * q, ua);
+        const double* ua = UQ + 3 * ((long)q * na + a);
         const double c = KA[(long)a * ldk + nkkt];
         u[0] += c * ua[0];
         u[1] += c * ua[1];
