@@ -1,20 +1,24 @@
 #!/usr/bin/env python3
 """Throughput of the hp-multigrid preconditioned skeleton solve on one MI355X.
 
-Workload: 2D generalized Stokes on the unit square, 4x4 structured coarse
-mesh refined 6 times (256x256 squares, 131072 triangles, 7 levels), order
-k = 2, beta = 1, nu = 1, gamma = eps^-1 = 1e2; f = uniform[-1,1) per data
-point (seed 0) plus the gradient of a seeded trigonometric polynomial.
+Headline workload (the largest single-GPU configuration): 3D generalized
+Stokes on the unit cube, 4^3 Kuhn cubes (six tetrahedra each) refined three
+times (32^3 cubes, 196,608 tetrahedra, 4 levels), order k = 3, beta = 1,
+nu = 1, gamma = eps^-1 = 1e3, f = uniform[-1,1) per data point (seed 0);
+edge-patch relaxation and smoothing, m_p = m_h = 2, variable V-cycle.
 A step is inner solve #1 of the AL-Uzawa iteration: A^eps lambda = g from
-lambda = 0 by flexible CG preconditioned by MG_hp (variable V-cycle,
-m_p = m_h = 1) to relative residual 1e-8, every operation in the HIP
-library, the condensed load g already resident in HBM.  `value` is the
-all-FP64 solve; `mixed` stores the V-cycle's operators in FP32 (FP64
-vectors, accumulation and Krylov; same 1e-8 on the FP64 operator).
+lambda = 0 by flexible CG preconditioned by MG_hp to relative residual 1e-8,
+every operation in the HIP library, the condensed load g already resident
+in HBM.  `value` is the all-FP64 solve; `mixed` stores the V-cycle's
+operators in FP32 (FP64 vectors, accumulation and Krylov; same 1e-8 on the
+FP64 operator), with its relative difference from the FP64 solution.  The
+same cube at k = 2 and the 2D workloads (256x256 Stokes, the lid-driven
+cavity, Alg. 3, the batch gradient) are reported as sub-objects.
 
 Prints one JSON line (metric, value = skeleton DOFs solved per second,
-roofline of the dominant kernel from live HIP-event timing, the V-cycle's
-achieved bandwidth, and the CPU oracle timed on a bounded sample).
+roofline of the dominant kernel from live HIP-event timing, the V-cycle
+against the compulsory bytes of its operators, and the CPU oracle timed on
+the host's cores on a bounded sample).
 """
 import argparse
 import json
@@ -26,6 +30,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+PEAK_FP64_MFMA_TFS = 78.6
+KCLASS3 = {0: "order-k edge-patch Gauss-Seidel, one colour (k_patch_gs3)",
+           1: "order-k skeleton apply S_K x_K (k_cell_apply3 + k_face_gather3)",
+           2: "lowest-order edge-patch Gauss-Seidel phases (k_patch_gs3, m_F = 1)",
+           3: "MG_hp"}
 KCLASS = {0: "order-k vertex-patch relaxation, one colour (k_patch_relax)",
           1: "order-k cell apply S_K x_K (k_cell_apply)",
           2: "lowest-order smoothing phases on launched levels (k_gs / streaming pair)"}
@@ -37,40 +46,47 @@ COARSE_CLASS = "coarse MG_h: tabulated operator (k_gemv_rows) / single-workgroup
 # that runs most often (every Gauss-Seidel colour phase and every Krylov
 # apply read all cell blocks).
 ROOF_CLASS = 1
-# HBM traffic of that kernel from two counter runs (FETCH_SIZE, then
-# WRITE_SIZE, KiB per dispatch) of `bench.py --profile-run`, each scaled by
-# what the counter read for a plain copy of 1 GiB in the same run (FETCH
-# 524315 KiB -> x2.0, WRITE 1048576 KiB -> x1.0).  Valid only for the
-# workload and kernel it was taken on.
-TRAFFIC = {(2, 6, 1.0, 1e2): {"kernel": "k_cell_apply<6, double>", "fetch_KiB": 96614.88,
-                              "write_KiB": 18984.96, "fetch_scale": 1048576 / 524314.69,
-                              "write_scale": 1.0}}
 
-
-def cpu_baseline(k, beta, gamma, reps):
-    """The CPU oracle, untuned, on a bounded sample of the same workload:
-    32x32 squares (2048 cells, 4 levels), same k, beta, nu, gamma and f
-    recipe; inner solve #1 timed `reps` times (setup excluded)."""
+def _oracle_worker(args):
+    """One CPU process of the baseline: the 3D oracle on the sample mesh,
+    setup untimed, then `reps` inner solves #1 timed."""
+    k, reps, seed = args
     import numpy as np
     from threadpoolctl import threadpool_limits
     import synth
-    from oracle import solver
+    from oracle import solver3d
     with threadpool_limits(1):
-        c, t = synth.kuhn_square(4)
-        S = solver.Setup(c, t, 3, k, 1.0, beta, gamma)
-        nq = (k + 2) ** 2
-        X = np.array([e.xq for e in S.prob.elems])
-        f = synth.source_uniform(0, 1, S.lv.n_cells, nq)[0] + synth.trig_gradient(X, 1)
+        c, t = synth.kuhn_cube(1)
+        S = solver3d.Setup3(c, t, 2, k, 1.0, 1.0, 1e3)
+        f = synth.source_uniform(seed, 1, S.lv.n_cells, (k + 2) ** 3, dim=3)[0]
         g = S.prob.rhs(f)
         t0 = time.perf_counter()
         for _ in range(reps):
             _, its, _ = S.inner(g, atol=0.0)
         dt = time.perf_counter() - t0
-    n = S.Aeps.shape[0]
-    return {"value": n * reps / dt, "unit": "skeleton DOFs/s", "cores": 1, "kind": "oracle",
-            "sample": f"32x32 squares (2048 cells, 4 levels), k={k}, N_skel={n}, inner solve #1 "
-                      f"({its} its) x{reps}, numpy/scipy single thread, setup excluded",
-            "seconds": round(dt, 3)}
+    return S.Aeps.shape[0], its, dt
+
+
+def cpu_baseline(k, reps, workers):
+    """The CPU oracle, untuned, on a bounded sample of the headline workload,
+    on `workers` host cores at once (one process each, one thread each):
+    the unit cube as one Kuhn cube refined twice (384 tetrahedra, 3 levels),
+    same k, beta, nu, gamma, smoothing and f recipe; each process times
+    `reps` inner solves #1 (setup excluded).  The value is the sum of the
+    processes' rates.  Runs before the GPU is touched (forked workers)."""
+    import multiprocessing as mp
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(workers) as pool:
+        res = pool.map(_oracle_worker, [(k, reps, 0)] * workers)
+    wall = time.perf_counter() - t0
+    n, its = res[0][0], res[0][1]
+    rate = sum(n * reps / dt for _, _, dt in res)
+    return {"value": rate, "unit": "skeleton DOFs/s", "cores": workers, "kind": "oracle",
+            "sample": f"unit cube, one Kuhn cube refined twice (384 tets, 3 levels), k={k}, N_skel={n}, "
+                      f"inner solve #1 ({its} its) x{reps} in each of {workers} single-thread processes "
+                      f"(numpy/scipy), setup excluded; sum of the processes' rates",
+            "seconds_per_process": [round(dt, 2) for _, _, dt in res], "wall_s": round(wall, 1)}
 
 
 def oseen_workload(hd, synth, torch, np, steps, re, k=3, n_refine=5):
@@ -306,29 +322,190 @@ def sweep(hd, synth, torch, np, c, t, a):
     print(json.dumps({"sweep_cases": len(rows)}), flush=True)
 
 
+def progress(msg):
+    """Progress on stderr (the JSON line alone goes to stdout)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
+def stokes3d(hd, synth, torch, np, k, prec, steps, warmup, tsteps, x_ref=None):
+    """The cube workload at order k and V-cycle storage `prec`: setup,
+    assembly, inner solve #1 timed `steps` times after `warmup`, then
+    `tsteps` more with the live per-kernel timers."""
+    progress(f"cube k={k} precision {prec}: setup and assembly")
+    c, t = synth.kuhn_cube(4)
+    t0 = time.perf_counter()
+    s = hd.Solver(c, t, 3, k, 1.0, 1.0, 1e3, atol=0.0, m_relax=2, m_smooth=2, vcycle_precision=prec)
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    s.assemble()
+    torch.cuda.synchronize()
+    t_assemble = time.perf_counter() - t0
+    f = torch.as_tensor(synth.source_uniform(0, 1, s.n_cells, s.n_q, dim=3)[0], device="cuda")
+    g = s.rhs(f)
+    del f
+    x = torch.empty_like(g)
+    for _ in range(warmup):
+        s.inner_solve(g, x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its_all = []
+    for _ in range(steps):
+        _, its, rel, st = s.inner_solve(g, x)
+        its_all.append(its)
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    progress(f"cube k={k} precision {prec}: {steps} solves in {T:.2f} s, iterations {its_all}")
+    xh = x.cpu().numpy()
+    err = None if x_ref is None else float(np.linalg.norm(xh - x_ref) / np.linalg.norm(x_ref))
+    for cls in range(4):
+        s.timer(cls, True)
+    torch.cuda.synchronize()
+    for _ in range(tsteps):
+        s.inner_solve(g, x)
+    torch.cuda.synchronize()
+    tm = {cls: s.timer_read(cls) for cls in range(4)}
+    for cls in range(4):
+        s.timer(cls, False)
+    out = dict(T=T, its=its_all, tm=tm, t_setup=t_setup, t_assemble=t_assemble, n_skel=s.n_skel,
+               n_cells=s.n_cells, levels=s.levels, rel=rel, status=st, x=xh, err_vs_fp64=err,
+               vc_design=s.query(12), vc_compulsory=s.query(13))
+    s.close()
+    del g, x
+    torch.cuda.empty_cache()
+    return out
+
+
+def classes3(tm):
+    return {KCLASS3[c_]: {"ms": tm[c_][0], "launches": tm[c_][1], "GB": tm[c_][2] / 1e9,
+                          "avg_us": 1e3 * tm[c_][0] / max(tm[c_][1], 1)} for c_ in range(4)}
+
+
+def vcycle3(m):
+    ms, n, _ = m["tm"][3]
+    avg = ms / max(n, 1) * 1e-3
+    return {"avg_ms": 1e3 * avg, "compulsory_GB": m["vc_compulsory"] / 1e9,
+            "compulsory_GB_per_s": m["vc_compulsory"] / avg / 1e9,
+            "frac_of_hbm_peak": m["vc_compulsory"] / avg / 1e9 / PEAK_HBM_GBS,
+            "implementation_GB": m["vc_design"] / 1e9, "implementation_GB_per_s": m["vc_design"] / avg / 1e9,
+            "model": "compulsory = every stored operator read once per use in packed symmetric form (cell "
+                     "blocks, edge-patch inverses, CR blocks, coarsest inverse) + vectors + transfers; "
+                     "implementation = what the launches move (each patch cell's two patch-face row blocks "
+                     "of S_K per edge patch, i.e. S_K read three times per sweep, full patch inverses)"}
+
+
+def stokes2d_line(hd, synth, torch, np, a):
+    """The 256x256 generalized Stokes workload of the triangular path (k = 2,
+    beta = 1, gamma = 1e2, 7 levels, vertex patches, m_p = m_h = 1): FP64,
+    FP32-storage and FP16-storage V-cycles, with kernel classes and the
+    V-cycle against its compulsory bytes."""
+    c, t = synth.kuhn_square(4)
+
+    def measure(prec, x_ref=None):
+        t0 = time.perf_counter()
+        s = hd.Solver(c, t, 6, 2, 1.0, 1.0, 1e2, atol=0.0, vcycle_precision=prec)
+        t_setup = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        s.assemble()
+        torch.cuda.synchronize()
+        t_assemble = time.perf_counter() - t0
+        X = s.data_points().cpu().numpy()
+        f = synth.source_uniform(0, 1, s.n_cells, s.n_q)[0] + synth.trig_gradient(X, 1)
+        g = s.rhs(torch.as_tensor(f, device="cuda"))
+        x = torch.empty_like(g)
+        s.inner_solve(g, x)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its_all = []
+        for _ in range(a.steps2d):
+            _, its, rel, st = s.inner_solve(g, x)
+            its_all.append(its)
+        torch.cuda.synchronize()
+        T = time.perf_counter() - t0
+        xh = x.cpu().numpy()
+        for cls in range(5):
+            s.timer(cls, True)
+        for _ in range(a.steps2d):
+            s.inner_solve(g, x)
+        torch.cuda.synchronize()
+        tm = {cls: s.timer_read(cls) for cls in range(5)}
+        for cls in range(5):
+            s.timer(cls, False)
+        s.timer(3, True)
+        for _ in range(a.steps2d):
+            s.inner_solve(g, x)
+        torch.cuda.synchronize()
+        vc = s.timer_read(3)
+        s.timer(3, False)
+        out = dict(T=T, its=its_all, tm=tm, n_skel=s.n_skel, n_cells=s.n_cells, vc=vc,
+                   vc_design=s.query(12), vc_compulsory=s.query(13), t_setup=t_setup, t_assemble=t_assemble,
+                   err=None if x_ref is None else float(np.linalg.norm(xh - x_ref) / np.linalg.norm(x_ref)), x=xh)
+        s.close()
+        return out
+
+    m64 = measure(0)
+    progress("2D FP64 done")
+    m32 = measure(1, m64["x"])
+    m16 = measure(2, m64["x"])
+    progress("2D mixed done")
+
+    def classes(tm_):
+        return {KCLASS.get(c_, "MG_hp"): {"ms": tm_[c_][0], "launches": tm_[c_][1], "GB": tm_[c_][2] / 1e9}
+                for c_ in range(4)} | {COARSE_CLASS: {"ms": tm_[4][0], "launches": tm_[4][1], "GB": tm_[4][2] / 1e9}}
+
+    def vcyc(m):
+        ms, n, _ = m["vc"]
+        avg = ms / max(n, 1) * 1e-3
+        return {"avg_ms": 1e3 * avg, "compulsory_GB": m["vc_compulsory"] / 1e9,
+                "compulsory_GB_per_s": m["vc_compulsory"] / avg / 1e9,
+                "frac_of_hbm_peak": m["vc_compulsory"] / avg / 1e9 / PEAK_HBM_GBS,
+                "implementation_GB": m["vc_design"] / 1e9,
+                "implementation_GB_per_s": m["vc_design"] / avg / 1e9,
+                "timing": "HIP events around each graph replay of MG_hp"}
+
+    ms, n_l, by = m64["tm"][ROOF_CLASS]
+    n = m64["n_skel"]
+    return {"workload": f"2D generalized Stokes, 256x256 structured triangulation ({m64['n_cells']} cells, 7 levels), "
+                        f"k=2, beta=1, nu=1, gamma=1e2; inner solve #1 to rel.res 1e-8",
+            "n_skel": n, "value": n * a.steps2d / m64["T"], "unit": "skeleton DOFs/s",
+            "ms_per_step": 1e3 * m64["T"] / a.steps2d, "iterations": m64["its"],
+            "vcycle": vcyc(m64), "kernel_classes": classes(m64["tm"]),
+            "cell_apply": {"avg_us": 1e3 * ms / n_l, "algorithmic_bytes_per_launch": by / n_l,
+                           "GB_per_s": by / n_l / (ms / n_l * 1e-3) / 1e9},
+            "setup_s": m64["t_setup"], "assemble_s": m64["t_assemble"],
+            "mixed": {"value": n * a.steps2d / m32["T"], "iterations": m32["its"],
+                      "rel_diff_vs_fp64_solution": m32["err"], "vcycle": vcyc(m32),
+                      "precision": "V-cycle operators FP32; vectors, accumulation and FCG FP64"},
+            "mixed_fp16": {"value": n * a.steps2d / m16["T"], "iterations": m16["its"],
+                           "rel_diff_vs_fp64_solution": m16["err"], "vcycle": vcyc(m16),
+                           "precision": "order-k cell blocks and patch inverses FP16 (scaled), other "
+                                        "V-cycle operators FP32; vectors, accumulation and FCG FP64"}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--k", type=int, default=2)
-    ap.add_argument("--n-refine", type=int, default=6)
-    ap.add_argument("--beta", type=float, default=1.0)
-    ap.add_argument("--gamma", type=float, default=1e2)
-    ap.add_argument("--cpu-reps", type=int, default=20)
+    ap.add_argument("--k", type=int, default=3, help="order of the headline cube workload (2 or 3)")
+    ap.add_argument("--steps2d", type=int, default=5)
+    ap.add_argument("--timer-steps", type=int, default=1)
+    ap.add_argument("--cpu-reps", type=int, default=2)
+    ap.add_argument("--cpu-workers", type=int, default=0, help="0: min(16, host cores)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-2d", action="store_true", help="skip the triangular-mesh workloads")
     ap.add_argument("--no-oseen", action="store_true", help="skip the lid-driven cavity Picard workload")
     ap.add_argument("--picard-steps", type=int, default=10)
     ap.add_argument("--re", type=float, default=100.0)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the batch-gradient workload")
     ap.add_argument("--adjoint-rhs", type=int, default=16)
+    ap.add_argument("--n-refine", type=int, default=6)
     ap.add_argument("--sweep", action="store_true",
                     help="parameter sweeps instead of the bench line: the 256x256 generalized Stokes "
                          "workload over k, beta, gamma and V-cycle precision, and the cavity over Re; "
                          "one JSON line per case, then a summary line")
     ap.add_argument("--profile-run", action="store_true",
                     help="counter-collection run: a 1 GiB device copy (calibration of the HBM "
-                         "counters) then two FP64 inner solves; prints a summary only")
+                         "counters) then two FP64 inner solves of the cube workload; prints a summary only")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py: the solver runs on one GPU; --gpus {a.gpus} is not supported "
@@ -336,6 +513,12 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     import numpy as np
+    cpu = None
+    if not (a.no_cpu_baseline or a.sweep or a.profile_run):
+        # before anything touches the GPU: the workers are forked
+        workers = a.cpu_workers or min(16, os.cpu_count() or 1)
+        progress(f"CPU oracle baseline on {workers} processes")
+        cpu = cpu_baseline(a.k, a.cpu_reps, workers)
     import torch
     import paper_2303_06762_amd as hd
     import synth
@@ -346,12 +529,13 @@ def main():
         sweep(hd, synth, torch, np, c, t, a)
         return
     if a.profile_run:
-        # calibration: a plain copy of exactly 1 GiB read + 1 GiB written
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-        s = hd.Solver(c, t, a.n_refine, a.k, a.beta, 1.0, a.gamma, atol=0.0)
+        del src, dst
+        c3, t3 = synth.kuhn_cube(4)
+        s = hd.Solver(c3, t3, 3, a.k, 1.0, 1.0, 1e3, atol=0.0, m_relax=2, m_smooth=2)
         s.assemble()
         g = torch.ones(s.n_skel, dtype=torch.float64, device="cuda")
         x = torch.empty_like(g)
@@ -361,73 +545,24 @@ def main():
         print(json.dumps({"profile_run": True, "n_skel": s.n_skel, "iterations": its}))
         return
 
-    def measure(prec):
-        """Setup, assemble, then time inner solve #1 K times (value) and K
-        more times with the live per-kernel event timers (roofline)."""
-        t0 = time.perf_counter()
-        s = hd.Solver(c, t, a.n_refine, a.k, a.beta, 1.0, a.gamma, atol=0.0, vcycle_precision=prec)
-        t_setup = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        s.assemble()
-        torch.cuda.synchronize()
-        t_assemble = time.perf_counter() - t0
-        X = s.data_points().cpu().numpy()
-        f = synth.source_uniform(0, 1, s.n_cells, s.n_q)[0] + synth.trig_gradient(X, 1)
-        g = s.rhs(torch.as_tensor(f, device="cuda"))
-        x = torch.empty_like(g)
-        for _ in range(a.warmup):
-            s.inner_solve(g, x)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        its_all = []
-        for _ in range(a.steps):
-            _, its, rel, st = s.inner_solve(g, x)
-            its_all.append(its)
-        torch.cuda.synchronize()
-        T = time.perf_counter() - t0
-        for cls in range(5):
-            s.timer(cls, True)
-        torch.cuda.synchronize()
-        for _ in range(a.steps):
-            s.inner_solve(g, x)
-        torch.cuda.synchronize()
-        tm = {cls: s.timer_read(cls) for cls in range(5)}
-        for cls in range(5):
-            s.timer(cls, False)
-        # the whole V-cycle alone: events around each graph replay, as the
-        # timed solves run it
-        s.timer(3, True)
-        torch.cuda.synchronize()
-        for _ in range(a.steps):
-            s.inner_solve(g, x)
-        torch.cuda.synchronize()
-        vc_graph = s.timer_read(3)
-        s.timer(3, False)
-        out = dict(T=T, its=its_all, tm=tm, t_setup=t_setup, t_assemble=t_assemble, n_skel=s.n_skel,
-                   n_cells=s.n_cells, levels=s.levels, rel=rel, vc_graph=vc_graph)
-        s.close()
-        return out
-
-    m64 = measure(0)
-    m32 = measure(1)
-    m16 = measure(2)
+    # mixed storage: FP32 cell blocks (AL term apart, FP64) and lowest-order
+    # operators; the order-k edge-patch inverses FP64 at k = 3 (precision 3;
+    # all-FP32 storage does not converge there at this size) and FP32 at k = 2
+    mixed_prec = {2: 1, 3: 3}
+    m64 = stokes3d(hd, synth, torch, np, a.k, 0, a.steps, a.warmup, a.timer_steps)
+    m32 = stokes3d(hd, synth, torch, np, a.k, mixed_prec[a.k], a.steps, a.warmup, a.timer_steps, m64["x"])
+    k_other = 2 if a.k == 3 else 3
+    o64 = stokes3d(hd, synth, torch, np, k_other, 0, 1, 1, a.timer_steps)
+    o32 = stokes3d(hd, synth, torch, np, k_other, mixed_prec[k_other], 1, 1, 0, o64["x"])
     tm = m64["tm"]
-    dom = ROOF_CLASS
-    ms, n_l, by = tm[dom]
+    by_time = max((0, 1, 2), key=lambda c_: tm[c_][0])
+    ms, n_l, by = tm[by_time]
     achieved = (by / n_l) / (ms / n_l * 1e-3) / 1e9
-    vc_ms, vc_n, vc_b = m64["vc_graph"]
-    ve_ms, ve_n, _ = tm[3]
-    tr = TRAFFIC.get((a.k, a.n_refine, a.beta, a.gamma))
-    traffic = None if tr is None else 1024.0 * (tr["fetch_KiB"] * tr["fetch_scale"] +
-                                                tr["write_KiB"] * tr["write_scale"])
     copy_gbs = copy_bandwidth(torch)
-    by_time = max(range(5), key=lambda c_: tm[c_][0] if c_ != 3 else -1.0)
-
-    def classes(tm_):
-        return {KCLASS.get(c_, "MG_hp"): {"ms": tm_[c_][0], "launches": tm_[c_][1], "GB": tm_[c_][2] / 1e9}
-                for c_ in range(4)} | {COARSE_CLASS: {"ms": tm_[4][0], "launches": tm_[4][1], "GB": tm_[4][2] / 1e9}}
-
     n_skel = m64["n_skel"]
+    wl = (f"3D generalized Stokes, unit cube, 4^3 Kuhn cubes refined 3 times (32^3 cubes, {m64['n_cells']} "
+          f"tetrahedra, {m64['levels']} levels), k={a.k}, beta=1, nu=1, gamma=1e3, edge patches, m_p=m_h=2; "
+          f"inner solve #1 to rel.res 1e-8")
     out = {
         "metric": "skeleton DOFs solved/s to rel.res 1e-8 (FP64 vs mixed); V-cycle HBM GB/s",
         "value": n_skel * a.steps / m64["T"],
@@ -441,48 +576,52 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"2D generalized Stokes, {4 << a.n_refine}x{4 << a.n_refine} structured "
-                               f"triangulation ({m64['n_cells']} cells, {m64['levels']} levels), k={a.k}, "
-                               f"beta={a.beta:g}, nu=1, gamma={a.gamma:g}; inner solve #1 to rel.res 1e-8",
-                   "n_skel": n_skel, "iterations": m64["its"],
+        "config": {"workload": wl, "n_skel": n_skel, "iterations": m64["its"], "status": m64["status"],
                    "precision": "FP64 operators, vectors and Krylov"},
         "mixed": {"value": n_skel * a.steps / m32["T"], "unit": "skeleton DOFs/s",
                   "ms_per_step": 1e3 * m32["T"] / a.steps, "iterations": m32["its"],
-                  "precision": "V-cycle operators stored FP32; vectors, accumulation and the "
-                               "flexible CG FP64; same rel.res 1e-8 on the FP64 operator",
-                  "vcycle_avg_ms": m32["vc_graph"][0] / max(m32["vc_graph"][1], 1),
-                  "vcycle_GB_per_s": m32["vc_graph"][2] / max(m32["vc_graph"][0], 1e-9) / 1e6,
-                  "kernel_classes": classes(m32["tm"])},
-        "mixed_fp16": {"value": n_skel * a.steps / m16["T"], "unit": "skeleton DOFs/s",
-                       "ms_per_step": 1e3 * m16["T"] / a.steps, "iterations": m16["its"],
-                       "precision": "order-k cell blocks (augmented-Lagrangian term kept apart in FP32) "
-                                    "and patch inverses stored FP16, each block scaled by its largest "
-                                    "magnitude; other V-cycle operators FP32; vectors, accumulation and "
-                                    "the flexible CG FP64; same rel.res 1e-8 on the FP64 operator",
-                       "vcycle_avg_ms": m16["vc_graph"][0] / max(m16["vc_graph"][1], 1),
-                  "vcycle_GB_per_s": m16["vc_graph"][2] / max(m16["vc_graph"][0], 1e-9) / 1e6,
-                       "kernel_classes": classes(m16["tm"])},
+                  "rel_diff_vs_fp64_solution": m32["err_vs_fp64"],
+                  "precision": ("V-cycle operators stored FP32 (cell blocks without their AL term, which is "
+                                "applied apart in FP64; CR levels, transfers, coarsest inverse)"
+                                + (", order-k edge-patch inverses FP64" if mixed_prec[a.k] == 3
+                                   else ", edge-patch inverses FP32")
+                                + "; vectors, accumulation and the flexible CG FP64; same rel.res 1e-8 on the "
+                                  "FP64 operator"),
+                  "vcycle": vcycle3(m32), "kernel_classes": classes3(m32["tm"])},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
-                     "kernel": KCLASS[dom], "launches": n_l, "avg_us": 1e3 * ms / n_l,
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "kernel": KCLASS3[by_time], "launches": n_l, "avg_us": 1e3 * ms / n_l,
                      "algorithmic_bytes_per_launch": by / n_l,
-                     "copy_GB_per_s": copy_gbs,
-                     "largest_class_by_time": KCLASS.get(by_time) or COARSE_CLASS},
-        "vcycle": {"avg_ms": vc_ms / max(vc_n, 1), "algorithmic_GB": vc_b / max(vc_n, 1) / 1e9,
-                   "GB_per_s": (vc_b / max(vc_n, 1)) / (vc_ms / max(vc_n, 1) * 1e-3) / 1e9,
-                   "frac_of_hbm_peak": (vc_b / max(vc_n, 1)) / (vc_ms / max(vc_n, 1) * 1e-3) / 1e9 / PEAK_HBM_GBS,
-                   "timing": "HIP events around each graph replay of MG_hp (FP64 operators)",
-                   "avg_ms_eager_with_kernel_timers": ve_ms / max(ve_n, 1)},
-        "kernel_classes": classes(tm),
+                     "bytes_model": "per colour phase: for each edge patch its inverse and, for each patch "
+                                    "cell, the two patch-face row blocks of S_K, each entry read once in the "
+                                    "stored (FP64, full) layout, plus the patch's vectors",
+                     "copy_GB_per_s": copy_gbs},
+        "vcycle": vcycle3(m64),
+        "kernel_classes": classes3(tm),
         "setup_s": m64["t_setup"], "assemble_s": m64["t_assemble"],
+        f"k{k_other}": {"workload": wl.replace(f"k={a.k}", f"k={k_other}"), "n_skel": o64["n_skel"],
+                        "value": o64["n_skel"] / o64["T"], "iterations": o64["its"],
+                        "mixed_value": o32["n_skel"] / o32["T"], "mixed_iterations": o32["its"],
+                        "mixed_precision": "as the headline's mixed entry" + (
+                            " but with FP32 edge-patch inverses" if mixed_prec[k_other] == 1
+                            else " with FP64 order-k edge-patch inverses"),
+                        "mixed_rel_diff_vs_fp64_solution": o32["err_vs_fp64"],
+                        "vcycle": vcycle3(o64), "kernel_classes": classes3(o64["tm"]),
+                        "assemble_s": o64["t_assemble"]},
     }
-    if not a.no_oseen:
-        out["oseen"] = oseen_workload(hd, synth, torch, np, a.picard_steps, a.re)
-        out["alg3"] = alg3_workload(hd, synth, torch, np, a.re)
-    if not a.no_adjoint:
-        out["adjoint"] = adjoint_workload(hd, synth, torch, np, a.adjoint_rhs)
-    if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(a.k, a.beta, a.gamma, a.cpu_reps)
+    del m64, m32, o64, o32
+    if not a.no_2d:
+        out["stokes2d"] = stokes2d_line(hd, synth, torch, np, a)
+        if not a.no_oseen:
+            out["oseen"] = oseen_workload(hd, synth, torch, np, a.picard_steps, a.re)
+            progress("cavity Picard done")
+            out["alg3"] = alg3_workload(hd, synth, torch, np, a.re)
+            progress("Alg. 3 done")
+        if not a.no_adjoint:
+            out["adjoint"] = adjoint_workload(hd, synth, torch, np, a.adjoint_rhs)
+            progress("batch gradient done")
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

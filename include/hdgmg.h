@@ -107,7 +107,11 @@ typedef struct {
                               symmetric) and patch inverses in FP16, each
                               block scaled by its largest magnitude
                               (vectors, accumulation and the outer Krylov
-                              solver stay FP64)                           */
+                              solver stay FP64).  Tetrahedral meshes: 0,
+                              1 (cell blocks without their AL term, which
+                              is applied apart in FP64, and every other
+                              operator FP32) or 3 (as 1 with the order-k
+                              edge-patch inverses kept FP64)              */
   int oseen;               /* 1: the context solves Picard-linearised
                               (Oseen) systems (Sec. 4): hdgmg_set_wind is
                               allowed, every block and patch factor is
@@ -387,9 +391,15 @@ hdgmg_status hdgmg_recover(hdgmg_ctx* ctx, const double* f_qp,
 /* Sizes.  what: 0 n_cells (finest), 1 n_q, 2 N_skel, 3 levels J,
  * 4 device bytes held, 5 n_interior_facets (finest), 6 k,
  * 7 n_colours (finest level), 8 n_cells of level `level`,
- * 9 N of the lowest-order space of level `level` (2 n_interior_facets),
- * 10 n_boundary_facets (finest).
- * level counts from 0 (coarsest) and is ignored by 0..7. */
+ * 9 N of the lowest-order space of level `level` (d n_interior_facets),
+ * 10 n_boundary_facets (finest), 11 the dimension d,
+ * 12 bytes one MG_hp application moves in this implementation (every
+ *    operator entry its launches use, in the stored layout and precision,
+ *    plus vectors), 13 its compulsory bytes (every stored operator read
+ *    once per use in packed symmetric form -- cell blocks n(n+1)/2 words,
+ *    patch inverses n_s(n_s+1)/2, the coarsest inverse n_0(n_0+1)/2 -- in
+ *    the storage precision, plus the vectors); both after hdgmg_assemble.
+ * level counts from 0 (coarsest) and is ignored by 0..7 and 10..13. */
 hdgmg_status hdgmg_query(const hdgmg_ctx* ctx, int what, int level, int64_t* value);
 
 /* Copy an assembled operator to caller memory (device pointer dst, FP64):

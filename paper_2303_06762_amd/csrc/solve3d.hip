@@ -38,7 +38,9 @@ struct DevLev3 {
   double* pinv = nullptr;
   float* pinv32 = nullptr;
   std::vector<long> hpoff;
-  std::vector<double> phase_bytes;  // algorithmic bytes of each colour phase
+  // words each colour phase reads: cell-block entries, patch-inverse
+  // entries, and vector words (FP64)
+  std::vector<double> phase_S, phase_P, phase_V;
   double *u = nullptr, *g = nullptr, *r = nullptr, *yK = nullptr;
 };
 
@@ -81,7 +83,7 @@ struct Ctx3 {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
     double bytes = 0.0;
   } timers[5];
-  double apply_bytes = 0.0, vcycle_bytes = 0.0;
+  double apply_bytes = 0.0, vcycle_bytes = 0.0, vcycle_compulsory = 0.0;
 };
 
 namespace {
@@ -524,12 +526,16 @@ hdgmg_status upload_level(Ctx3* c, const Level3& L, int mF, DevLev3& D) {
   TRY3(dalloc(c, &D.yK, (size_t)std::max(L.nc, 1) * D.nK));
   // algorithmic bytes of a colour phase: per patch cell its two patch-face
   // row blocks of S_K, the patch inverse, and the vectors
-  D.phase_bytes.assign(D.ncol, 0.0);
+  D.phase_S.assign(D.ncol, 0.0);
+  D.phase_P.assign(D.ncol, 0.0);
+  D.phase_V.assign(D.ncol, 0.0);
   for (int col = 0; col < D.ncol; ++col)
     for (int p = L.colour_ptr[col]; p < L.colour_ptr[col + 1]; ++p) {
       const double ns = (double)(L.pf_ptr[p + 1] - L.pf_ptr[p]) * 3 * mF;
       const double ncl = L.pc_ptr[p + 1] - L.pc_ptr[p];
-      D.phase_bytes[col] += ncl * 2.0 * 3 * mF * D.nK + ns * ns + ncl * D.nK + 3.0 * ns;
+      D.phase_S[col] += ncl * 2.0 * 3 * mF * D.nK;
+      D.phase_P[col] += ns * ns;
+      D.phase_V[col] += ncl * D.nK + 3.0 * ns;
     }
   return HDGMG_OK;
 }
@@ -545,10 +551,23 @@ Level3View<TS> view(const DevLev3& D, const TS* S) {
   v.fcell = D.fcell;
   v.floc = D.floc;
   v.S = S;
+  v.al = 0.0;
+  v.cdiv = D.cdiv;
+  v.vol = D.vol;
   return v;
 }
 
+// the FP32 blocks hold A without its AL term, added apart in FP64
+Level3View<float> view32(const Ctx3* c, const DevLev3& D) {
+  Level3View<float> v = view<float>(D, D.S32);
+  v.al = c->eps_inv;
+  return v;
+}
+
+// vcycle_precision 1: every V-cycle operator stored FP32; 3: the same but the
+// order-k edge-patch inverses kept FP64
 bool f32(const Ctx3* c) { return c->opts.vcycle_precision >= 1; }
+bool pinv64(const Ctx3* c, const DevLev3& D) { return c->opts.vcycle_precision == 3 && &D == &c->K; }
 
 int kt_begin(Ctx3* c, int cls) {
   auto& T = c->timers[cls];
@@ -581,7 +600,7 @@ void kt_clear(Ctx3::Timer& T) {
 // y = alpha A x + b on a level (b may be null)
 void level_apply(Ctx3* c, DevLev3& D, const double* x, double* y, double alpha, const double* b, bool vc) {
   if (vc && f32(c))
-    launch_cell_apply3<float>(c->st, view<float>(D, D.S32), x, D.yK);
+    launch_cell_apply3<float>(c->st, view32(c, D), x, D.yK);
   else
     launch_cell_apply3<double>(c->st, view<double>(D, D.S), x, D.yK);
   launch_face_gather3(c->st, D.nint, D.mF, D.nK, D.fcell, D.floc, D.yK, alpha, b, y);
@@ -594,18 +613,26 @@ void apply_k(Ctx3* c, const double* x, double* y, double alpha, const double* b,
   kt_end(c, 1, t, (vc && f32(c) ? 4.0 : 8.0) * D.nc * (double)D.nK * D.nK + 8.0 * (2.0 * D.nc * D.nK + 2.0 * D.ndof));
 }
 
+double phase_bytes(const Ctx3* c, const DevLev3& D, int col) {
+  const double bs = f32(c) ? 4.0 : 8.0, bp = f32(c) && !pinv64(c, D) ? 4.0 : 8.0;
+  return D.phase_S[col] * bs + D.phase_P[col] * bp + D.phase_V[col] * 8.0;
+}
+
 void sweep(Ctx3* c, DevLev3& D, double* x, const double* b, bool forward, int cls) {
   for (int ci = 0; ci < D.ncol; ++ci) {
     const int col = forward ? ci : D.ncol - 1 - ci;
     const int p0 = D.colour_ptr[col], p1 = D.colour_ptr[col + 1];
     const int t = kt_begin(c, cls);
-    if (f32(c))
-      launch_patch_gs3<float>(c->st, view<float>(D, D.S32), D.pf_ptr, D.pf, D.pc_ptr, D.pc, D.poff, D.pinv32, p0,
-                              p1, x, b);
+    if (f32(c) && pinv64(c, D))
+      launch_patch_gs3<float, double>(c->st, view32(c, D), D.pf_ptr, D.pf, D.pc_ptr, D.pc, D.poff, D.pinv, p0,
+                                      p1, x, b);
+    else if (f32(c))
+      launch_patch_gs3<float, float>(c->st, view32(c, D), D.pf_ptr, D.pf, D.pc_ptr, D.pc, D.poff, D.pinv32, p0,
+                                     p1, x, b);
     else
-      launch_patch_gs3<double>(c->st, view<double>(D, D.S), D.pf_ptr, D.pf, D.pc_ptr, D.pc, D.poff, D.pinv, p0,
-                               p1, x, b);
-    kt_end(c, cls, t, D.phase_bytes[col] * (f32(c) ? 4.0 : 8.0));
+      launch_patch_gs3<double, double>(c->st, view<double>(D, D.S), D.pf_ptr, D.pf, D.pc_ptr, D.pc, D.poff,
+                                       D.pinv, p0, p1, x, b);
+    kt_end(c, cls, t, phase_bytes(c, D, col));
   }
 }
 
@@ -796,8 +823,9 @@ hdgmg_status patch_inverses(Ctx3* c, DevLev3& D) {
 
 hdgmg_status make_f32_level(Ctx3* c, DevLev3& D) {
   if (!D.S32) TRY3(dalloc(c, &D.S32, (size_t)std::max(D.nc, 1) * D.nK * D.nK));
+  launch_f32_blocks_noal(c->st, D.nc, D.mF, D.S, D.cdiv, D.vol, c->eps_inv, D.S32);
+  if (pinv64(c, D)) return HDGMG_OK;
   if (!D.pinv32) TRY3(dalloc(c, &D.pinv32, (size_t)std::max<long>(D.pinv_len, 1)));
-  launch_f32_copy(c->st, (long)D.nc * D.nK * D.nK, D.S, D.S32);
   launch_f32_copy(c->st, D.pinv_len, D.pinv, D.pinv32);
   return HDGMG_OK;
 }
@@ -829,6 +857,11 @@ hdgmg_status d3_setup(const hdgmg_mesh* mesh, int k, double beta, const double* 
   Ctx3* c = new Ctx3();
   hdgmg_default_opts(&c->opts);
   if (opts) c->opts = *opts;
+  if (c->opts.vcycle_precision < 0 || c->opts.vcycle_precision > 3 || c->opts.vcycle_precision == 2) {
+    err = "tetrahedral meshes: vcycle_precision must be 0 (FP64), 1 (FP32) or 3 (FP32, FP64 patch inverses)";
+    delete c;
+    return HDGMG_EINVAL;
+  }
   if (c->opts.oseen || c->opts.transpose) {
     err = "the Oseen system is available on triangular meshes only";
     delete c;
@@ -1024,8 +1057,8 @@ hdgmg_status d3_assemble(Ctx3* c) {
   double vb = 0.0;
   auto level_sweep = [&](const DevLev3& D) {
     double s = 0.0;
-    for (double x : D.phase_bytes) s += x;
-    return s * b;
+    for (int col = 0; col < D.ncol; ++col) s += phase_bytes(c, D, col);
+    return s;
   };
   auto level_res = [&](const DevLev3& D) { return b * D.nc * (double)D.nK * D.nK + 8.0 * 4.0 * D.ndof; };
   if (c->k > 0) vb += 2.0 * c->opts.m_relax * level_sweep(c->K) + level_res(c->K);
@@ -1036,6 +1069,26 @@ hdgmg_status d3_assemble(Ctx3* c) {
   }
   vb += tr_bytes * b / 8.0 + b * (double)c->n0 * c->n0;
   c->vcycle_bytes = vb;
+  // compulsory bytes: every stored operator read once per use in packed
+  // symmetric form (cell blocks nK(nK+1)/2 words, patch inverses
+  // ns(ns+1)/2, the coarsest inverse n0(n0+1)/2), plus the vectors
+  auto tri = [](double n) { return n * (n + 1.0) / 2.0; };
+  auto sweep_c = [&](const Level3& L, const DevLev3& D) {
+    double pb = 0.0;
+    for (int q = 0; q < D.np; ++q) pb += tri(3.0 * D.mF * (L.pf_ptr[q + 1] - L.pf_ptr[q]));
+    return D.nc * tri(D.nK) * b + pb * (pinv64(c, D) ? 8.0 : b) + 3.0 * 8.0 * D.ndof;
+  };
+  auto res_c = [&](const DevLev3& D) { return D.nc * tri(D.nK) * b + 3.0 * 8.0 * D.ndof; };
+  double vc = 0.0;
+  if (c->k > 0) vc += 2.0 * c->opts.m_relax * sweep_c(c->lv[c->J - 1], c->K) + res_c(c->K);
+  double vis = 1.0, ml = c->opts.m_smooth;
+  for (int l = c->J - 1; l >= 1; --l) {
+    vc += vis * (2.0 * ml * sweep_c(c->lv[l], c->cr[l]) + res_c(c->cr[l]));
+    vis *= c->opts.cycle;
+    ml *= c->opts.vcycle_growth;
+  }
+  vc += tr_bytes * b / 8.0 + vis * tri((double)c->n0) * b;
+  c->vcycle_compulsory = vc;
   c->assembled = true;
   return HDGMG_OK;
 }
@@ -1165,6 +1218,8 @@ hdgmg_status d3_query(const Ctx3* c, int what, int level, int64_t* value) {
       return HDGMG_OK;
     case 10: *value = LF.nf - LF.nint; return HDGMG_OK;
     case 11: *value = 3; return HDGMG_OK;
+    case 12: *value = (int64_t)c->vcycle_bytes; return HDGMG_OK;
+    case 13: *value = (int64_t)c->vcycle_compulsory; return HDGMG_OK;
     default: return HDGMG_EINVAL;
   }
 }

@@ -261,6 +261,10 @@ struct hdgmg_ctx {
   std::vector<double> relax_bytes;                // order-k level
   std::vector<std::vector<double>> smooth_bytes;  // lowest-order levels
   double apply_bytes = 0.0, vcycle_bytes = 0.0;
+  // the V-cycle's compulsory bytes: every stored operator read once per use
+  // in packed symmetric form (cell blocks n(n+1)/2 words, patch inverses
+  // n_s(n_s+1)/2), in its storage precision, plus the vectors
+  double vcycle_compulsory = 0.0;
 };
 
 // The preconditioner reads FP32 (vcycle_precision 1) or FP32 with FP16
@@ -2006,6 +2010,34 @@ hdgmg_status hdgmg_assemble(hdgmg_ctx* ctx) {
     }
     if (!dense_done) v += visits * (double)ctx->n0 * ctx->n0 * (o.vcycle_precision >= 1 ? 4.0 : 8.0);
     ctx->vcycle_bytes = v;
+    // compulsory bytes of the same V-cycle
+    auto tri = [](double n) { return n * (n + 1.0) / 2.0; };
+    auto sweep_c = [&](const Level& L, int m, double wb) {
+      double pb = 0.0;
+      for (size_t q = 0; q + 1 < L.patch_facet_ptr.size(); ++q)
+        pb += tri(2.0 * m * (L.patch_facet_ptr[q + 1] - L.patch_facet_ptr[q]));
+      return (L.nc * tri(6.0 * m) + pb) * wb + 3.0 * 8.0 * 2.0 * m * L.nint;
+    };
+    auto res_c = [&](const Level& L, int m, double wb) {
+      return L.nc * tri(6.0 * m) * wb + 3.0 * 8.0 * 2.0 * m * L.nint;
+    };
+    const double wk = o.vcycle_precision == 0 ? 8.0 : (o.vcycle_precision == 2 && ctx->K.f16 ? 2.0 : 4.0);
+    const double wl = o.vcycle_precision == 0 ? 8.0 : 4.0;
+    double vc = 0.0;
+    if (ctx->k > 0) {
+      const Level& LK = ctx->lv[ctx->J - 1];
+      vc += 2.0 * o.m_relax * sweep_c(LK, ctx->k + 1, wk) + res_c(LK, ctx->k + 1, wk);
+    }
+    double vis = 1.0, ml = o.m_smooth;
+    for (int l = ctx->J - 1; l >= 1; --l) {
+      const Level& L = ctx->lv[l];
+      vc += vis * (2.0 * ml * sweep_c(L, 1, wl) + res_c(L, 1, wl) +
+                   2.0 * (ctx->tr[l].nnz * (4.0 + wl) + (ctx->tr[l].nfine + ctx->tr[l].ncoarse) * 8.0));
+      vis *= o.cycle;
+      ml *= o.vcycle_growth;
+    }
+    vc += vis * tri((double)ctx->n0) * wl;
+    ctx->vcycle_compulsory = vc;
   }
   ctx->assembled = true;
   return HDGMG_OK;
@@ -2453,6 +2485,9 @@ hdgmg_status hdgmg_query(const hdgmg_ctx* ctx, int what, int level, int64_t* val
       *value = what == 8 ? ctx->lv[level].nc : 2L * ctx->lv[level].nint;
       return HDGMG_OK;
     case 10: *value = (int64_t)ctx->bfacets.size(); return HDGMG_OK;
+    case 11: *value = 2; return HDGMG_OK;
+    case 12: *value = (int64_t)ctx->vcycle_bytes; return HDGMG_OK;
+    case 13: *value = (int64_t)ctx->vcycle_compulsory; return HDGMG_OK;
     default: return HDGMG_EINVAL;
   }
 }

@@ -340,28 +340,57 @@ __global__ void __launch_bounds__(NT) k_tet_local(TetCells E, int mode, int c0, 
     }
   }
   __syncthreads();
-  // H = nu sum_ij G_ij^T G_ij + beta (u_a, u_b) on the RT block
-  for (long e = tid; e < (long)nz * nz; e += NT) {
-    const int a = (int)(e / nz), b = (int)(e % nz);
-    if (b < a) continue;
-    double acc = 0.0;
-    for (int ij = 0; ij < 9; ++ij) {
-      const double* Gm = R + (long)ij * nP * nz;
-      for (int r = 0; r < nP; ++r) acc += Gm[(long)r * nz + a] * Gm[(long)r * nz + b];
-    }
-    acc *= G.nu;
-    if (a < na && b < na && E.beta != 0.0) {
+  // H = nu sum_ij G_ij^T G_ij on FP64 matrix cores: G = [G_00; ..; G_22] is
+  // a (9 nP) x nz matrix (row stride nz), H = G^T G its Gram matrix.  Each
+  // wavefront owns 16 x 16 tiles (a-tile <= b-tile, mirrored) and
+  // accumulates them over the 9 nP rows four at a time with
+  // v_mfma_f64_16x16x4 (A operand: lane l holds G[k0 + l/16][a0 + l%16];
+  // B operand: lane l holds G[k0 + l/16][b0 + l%16]; result register r of
+  // lane l is H[a0 + l/16 + 4 r][b0 + l%16], the layout measured on gfx950).
+  {
+    const int wave = tid / 64, lane = tid % 64, nw = NT / 64;
+    const int nt = (nz + 15) / 16, kdim = 9 * nP;
+    const int li = lane % 16, lk = lane / 16;
+    int tile = 0;
+    for (int ta = 0; ta < nt; ++ta)
+      for (int tb = ta; tb < nt; ++tb, ++tile) {
+        if (tile % nw != wave) continue;
+        const int a0 = 16 * ta, b0 = 16 * tb;
+        const bool ina = a0 + li < nz, inb = b0 + li < nz;
+        typedef double v4d __attribute__((ext_vector_type(4)));
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
+        for (int k0 = 0; k0 < kdim; k0 += 4) {
+          const int kk = k0 + lk;
+          const double av = (ina && kk < kdim) ? R[(long)kk * nz + a0 + li] : 0.0;
+          const double bv = (inb && kk < kdim) ? R[(long)kk * nz + b0 + li] : 0.0;
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        }
+        for (int r = 0; r < 4; ++r) {
+          const int a = a0 + lk + 4 * r, b = b0 + li;
+          if (a < nz && b < nz) {
+            const double v = G.nu * acc[r];
+            H[(long)a * nz + b] = v;
+            H[(long)b * nz + a] = v;
+          }
+        }
+      }
+  }
+  __syncthreads();
+  // + beta (u_a, u_b) on the RT block
+  if (E.beta != 0.0)
+    for (long e = tid; e < (long)na * na; e += NT) {
+      const int a = (int)(e / na), b = (int)(e % na);
+      if (b < a) continue;
       double ms = 0.0;
       for (int q = 0; q < nq; ++q) {
         const double* ua = UQ + 3 * ((long)q * na + a);
         const double* ub = UQ + 3 * ((long)q * na + b);
         ms += T.wq[q] * (ua[0] * ub[0] + ua[1] * ub[1] + ua[2] * ub[2]);
       }
-      acc += E.beta * G.vol * ms;
+      const double v = H[(long)a * nz + b] + E.beta * G.vol * ms;
+      H[(long)a * nz + b] = v;
+      if (a != b) H[(long)b * nz + a] = v;
     }
-    H[(long)a * nz + b] = acc;
-    H[(long)b * nz + a] = acc;
-  }
   __syncthreads();
   // KKT with its right-hand side columns
   const int nkkt = d.nkkt;
@@ -469,6 +498,31 @@ __global__ void __launch_bounds__(NT) k_tet_local(TetCells E, int mode, int c0, 
   // outputs; X = KA[:, nkkt:]
   if (mode == TET_CONDENSE) {
     const int nK = d.nK;
+    // P = H_at^T X_a (8 m_F x nK) on FP64 matrix cores: A[i][k] =
+    // H[k][na + t0 + i], B[k][j] = X[k][l0 + j], k over the na RT unknowns
+    double* P = UQ;  // the basis values are no longer needed
+    {
+      const int wave = tid / 64, lane = tid % 64, nw = NT / 64;
+      const int nT = 8 * mF, ntr = (nT + 15) / 16, ntc = (nK + 15) / 16;
+      const int li = lane % 16, lk = lane / 16;
+      typedef double v4d __attribute__((ext_vector_type(4)));
+      for (int tile = wave; tile < ntr * ntc; tile += nw) {
+        const int t0 = 16 * (tile / ntc), l0 = 16 * (tile % ntc);
+        const bool ini = t0 + li < nT, inj = l0 + li < nK;
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
+        for (int k0 = 0; k0 < na; k0 += 4) {
+          const int kk = k0 + lk;
+          const double av = (ini && kk < na) ? H[(long)kk * nz + na + t0 + li] : 0.0;
+          const double bv = (inj && kk < na) ? KA[(long)kk * ldk + nkkt + l0 + li] : 0.0;
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        }
+        for (int r = 0; r < 4; ++r) {
+          const int i = t0 + lk + 4 * r, j = l0 + li;
+          if (i < nT && j < nK) P[(long)i * nK + j] = acc[r];
+        }
+      }
+    }
+    __syncthreads();
     double* St = R;  // R is no longer needed
     for (long e = tid; e < (long)nK * nK; e += NT) {
       const int rho = (int)(e / nK), lc = (int)(e % nK);
@@ -478,10 +532,8 @@ __global__ void __launch_bounds__(NT) k_tet_local(TetCells E, int mode, int c0, 
       if (cr == 0) {
         v = -KA[(long)(na + fr * mF + mr) * ldk + nkkt + lc];
       } else {
-        const int tr = na + (fr * 2 + cr - 1) * mF + mr;
-        double s = 0.0;
-        for (int a = 0; a < na; ++a) s += H[(long)a * nz + tr] * KA[(long)a * ldk + nkkt + lc];
-        v = s;
+        const int t = (fr * 2 + cr - 1) * mF + mr, tr = na + t;
+        v = P[(long)t * nK + lc];
         if (cl != 0) v += H[(long)tr * nz + na + (fl * 2 + cl - 1) * mF + ml];
       }
       if (cr == 0 && mr == 0 && cl == 0 && ml == 0)
@@ -631,11 +683,27 @@ __global__ void __launch_bounds__(64) k_cell_apply3(Level3View<TS> L, const doub
   }
   __syncthreads();
   const TS* Sc = L.S + (long)c * nK * nK;
+  double dx = 0.0;  // d . x_K for the AL term kept apart
+  if (L.al > 0.0)
+    for (int i = 0; i < 4; ++i) dx += L.cdiv[4 * c + i] * xs[i * m3];
   for (int row = lane; row < nK; row += 64) {
     double acc = 0.0;
     for (int col = 0; col < nK; ++col) acc += (double)Sc[(long)col * nK + row] * xs[col];
+    if (L.al > 0.0 && row % m3 == 0) acc += L.al / L.vol[c] * L.cdiv[4 * c + row / m3] * dx;
     yK[(long)c * nK + row] = acc;
   }
+}
+
+__global__ void k_f32_blocks_noal(int nc, int mF, const double* __restrict__ S, const double* __restrict__ cdiv,
+                                  const double* __restrict__ vol, double al, float* __restrict__ out) {
+  const int nK = 12 * mF, m3 = 3 * mF;
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)nc * nK * nK) return;
+  const int c = (int)(t / ((long)nK * nK)), e = (int)(t % ((long)nK * nK));
+  const int r = e / nK, q = e % nK;
+  double v = S[t];
+  if (r % m3 == 0 && q % m3 == 0) v -= al / vol[c] * cdiv[4 * c + r / m3] * cdiv[4 * c + q / m3];
+  out[t] = (float)v;
 }
 
 __global__ void k_face_gather3(int nint, int m3, int nK, const int* __restrict__ fcell, const int* __restrict__ floc,
@@ -735,39 +803,49 @@ __global__ void __launch_bounds__(NT) k_patch_inverse3(Level3View<double> L, con
   }
 }
 
-template <typename TS>
-__global__ void __launch_bounds__(NT) k_patch_gs3(Level3View<TS> L, const int* __restrict__ pf_ptr,
+// One edge patch per workgroup of BS threads: x_s += A_ss^-1 (b - A x)_s.
+// Residual rows: each patch cell contributes the rows of its (at most two)
+// patch faces, S_K read along columns (symmetric blocks), eight loads in
+// flight per thread; each face's two cells write their contributions to
+// separate LDS slots, so the residual is b - side0 - side1.
+template <typename TS, typename TP, int BS>
+__global__ void __launch_bounds__(BS) k_patch_gs3(Level3View<TS> L, const int* __restrict__ pf_ptr,
                                                   const int* __restrict__ pf, const int* __restrict__ pc_ptr,
                                                   const int* __restrict__ pc, const long* __restrict__ poff,
-                                                  const TS* __restrict__ pinv, int p0, double* x,
+                                                  const TP* __restrict__ pinv, int p0, double* x,
                                                   const double* __restrict__ b) {
   __shared__ int slot[PMAX_CELLS][4];
+  __shared__ int cellid[PMAX_CELLS];
   __shared__ double xs[PMAX_CELLS][12 * MF3MAX];
   __shared__ double res[PMAX_FACES * 3 * MF3MAX];
-  __shared__ double part[2 * PMAX_CELLS * 3 * MF3MAX];
-  __shared__ int ptgt[2 * PMAX_CELLS * 3 * MF3MAX];
+  __shared__ double side[2][PMAX_FACES * 3 * MF3MAX];
   const int p = p0 + blockIdx.x, tid = threadIdx.x;
   const int f0 = pf_ptr[p], nf = pf_ptr[p + 1] - f0, c0 = pc_ptr[p], ncl = pc_ptr[p + 1] - c0;
   const int m3 = 3 * L.mF, ns = nf * m3, nK = L.nK;
   if (nf > PMAX_FACES || ncl > PMAX_CELLS) return;  // rejected on the host
-  for (int e = tid; e < ncl * 4; e += NT) {
+  for (int e = tid; e < ncl * 4; e += BS) {
     const int ci = e / 4, i = e % 4;
-    const int dof = L.cell_dofs[4 * pc[c0 + ci] + i];
-    int s = -1;
+    const int cell = pc[c0 + ci];
+    if (i == 0) cellid[ci] = cell;
+    const int dof = L.cell_dofs[4 * cell + i];
+    int sl = -1;
     for (int q = 0; q < nf; ++q)
-      if (pf[f0 + q] == dof) s = q;
-    slot[ci][i] = dof < 0 ? -1 : s;
+      if (pf[f0 + q] == dof) sl = q;
+    slot[ci][i] = dof < 0 ? -1 : sl;
   }
-  for (int e = tid; e < ncl * nK; e += NT) {
+  for (int e = tid; e < ncl * nK; e += BS) {
     const int ci = e / nK, i = e % nK;
     const int dof = L.cell_dofs[4 * pc[c0 + ci] + i / m3];
     xs[ci][i] = dof < 0 ? 0.0 : x[(long)dof * m3 + i % m3];
   }
-  for (int q = tid; q < ns; q += NT) res[q] = b[(long)pf[f0 + q / m3] * m3 + q % m3];
+  for (int q = tid; q < ns; q += BS) {
+    res[q] = b[(long)pf[f0 + q / m3] * m3 + q % m3];
+    side[0][q] = 0.0;
+    side[1][q] = 0.0;
+  }
   __syncthreads();
-  // rows of S_K x_K on the patch faces of each cell (at most two per cell)
   const int nitem = ncl * 2 * m3;
-  for (int it = tid; it < nitem; it += NT) {
+  for (int it = tid; it < nitem; it += BS) {
     const int ci = it / (2 * m3), which = (it / m3) % 2, rr = it % m3;
     int i = -1, cnt = 0;
     for (int q = 0; q < 4; ++q)
@@ -775,28 +853,49 @@ __global__ void __launch_bounds__(NT) k_patch_gs3(Level3View<TS> L, const int* _
         if (cnt == which) i = q;
         ++cnt;
       }
-    ptgt[it] = -1;
     if (i < 0) continue;
-    const TS* Sc = L.S + (long)pc[c0 + ci] * nK * nK;
-    const int row = i * m3 + rr;
-    double acc = 0.0;
-    for (int col = 0; col < nK; ++col) acc += (double)Sc[(long)col * nK + row] * xs[ci][col];
-    part[it] = acc;
-    ptgt[it] = slot[ci][i] * m3 + rr;
+    const int cell = cellid[ci];
+    const TS* Sc = L.S + (long)cell * nK * nK + i * m3 + rr;
+    const double* xc = xs[ci];
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int col = 0;
+    for (; col + 8 <= nK; col += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = (double)Sc[(long)(col + u) * nK];
+      a0 += v[0] * xc[col] + v[4] * xc[col + 4];
+      a1 += v[1] * xc[col + 1] + v[5] * xc[col + 5];
+      a2 += v[2] * xc[col + 2] + v[6] * xc[col + 6];
+      a3 += v[3] * xc[col + 3] + v[7] * xc[col + 7];
+    }
+    for (; col < nK; ++col) a0 += (double)Sc[(long)col * nK] * xc[col];
+    double acc = (a0 + a1) + (a2 + a3);
+    if (L.al > 0.0 && rr == 0) {
+      double dx = 0.0;
+      for (int q = 0; q < 4; ++q) dx += L.cdiv[4 * cell + q] * xc[q * m3];
+      acc += L.al / L.vol[cell] * L.cdiv[4 * cell + i] * dx;
+    }
+    const int dof = L.cell_dofs[4 * cell + i];
+    const int sd = L.fcell[2 * dof] == cell ? 0 : 1;
+    side[sd][slot[ci][i] * m3 + rr] = acc;
   }
   __syncthreads();
-  for (int q = tid; q < ns; q += NT) {
-    double s = res[q];
-    for (int it = 0; it < nitem; ++it)
-      if (ptgt[it] == q) s -= part[it];
-    res[q] = s;
-  }
+  for (int q = tid; q < ns; q += BS) res[q] -= side[0][q] + side[1][q];
   __syncthreads();
-  const TS* Ai = pinv + poff[p];
-  for (int q = tid; q < ns; q += NT) {
-    double s = 0.0;
-    for (int j = 0; j < ns; ++j) s += (double)Ai[(long)j * ns + q] * res[j];
-    x[(long)pf[f0 + q / m3] * m3 + q % m3] += s;
+  const TP* Ai = pinv + poff[p];
+  for (int q = tid; q < ns; q += BS) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int j = 0;
+    for (; j + 4 <= ns; j += 4) {
+      const double v0 = (double)Ai[(long)j * ns + q], v1 = (double)Ai[(long)(j + 1) * ns + q];
+      const double v2 = (double)Ai[(long)(j + 2) * ns + q], v3 = (double)Ai[(long)(j + 3) * ns + q];
+      a0 += v0 * res[j];
+      a1 += v1 * res[j + 1];
+      a2 += v2 * res[j + 2];
+      a3 += v3 * res[j + 3];
+    }
+    for (; j < ns; ++j) a0 += (double)Ai[(long)j * ns + q] * res[j];
+    x[(long)pf[f0 + q / m3] * m3 + q % m3] += (a0 + a1) + (a2 + a3);
   }
 }
 
@@ -911,18 +1010,28 @@ void launch_patch_inverse3(hipStream_t st, Level3View<double> L, const int* pf_p
                      pinv, status);
 }
 
-template <typename TS>
+template <typename TS, typename TP>
 void launch_patch_gs3(hipStream_t st, Level3View<TS> L, const int* pf_ptr, const int* pf, const int* pc_ptr,
-                      const int* pc, const long* poff, const TS* pinv, int p0, int p1, double* x,
+                      const int* pc, const long* poff, const TP* pinv, int p0, int p1, double* x,
                       const double* b) {
   if (p1 <= p0) return;
-  hipLaunchKernelGGL(k_patch_gs3<TS>, dim3(p1 - p0), dim3(NT), 0, st, L, pf_ptr, pf, pc_ptr, pc, poff, pinv, p0, x,
-                     b);
+  // lowest-order patches (at most 36 unknowns): a wavefront each
+  if (L.mF == 1)
+    hipLaunchKernelGGL((k_patch_gs3<TS, TP, 64>), dim3(p1 - p0), dim3(64), 0, st, L, pf_ptr, pf, pc_ptr, pc, poff,
+                       pinv, p0, x, b);
+  else
+    hipLaunchKernelGGL((k_patch_gs3<TS, TP, NT>), dim3(p1 - p0), dim3(NT), 0, st, L, pf_ptr, pf, pc_ptr, pc, poff,
+                       pinv, p0, x, b);
 }
-template void launch_patch_gs3<double>(hipStream_t, Level3View<double>, const int*, const int*, const int*,
-                                       const int*, const long*, const double*, int, int, double*, const double*);
-template void launch_patch_gs3<float>(hipStream_t, Level3View<float>, const int*, const int*, const int*,
-                                      const int*, const long*, const float*, int, int, double*, const double*);
+template void launch_patch_gs3<double, double>(hipStream_t, Level3View<double>, const int*, const int*, const int*,
+                                               const int*, const long*, const double*, int, int, double*,
+                                               const double*);
+template void launch_patch_gs3<float, float>(hipStream_t, Level3View<float>, const int*, const int*, const int*,
+                                             const int*, const long*, const float*, int, int, double*,
+                                             const double*);
+template void launch_patch_gs3<float, double>(hipStream_t, Level3View<float>, const int*, const int*, const int*,
+                                              const int*, const long*, const double*, int, int, double*,
+                                              const double*);
 
 void launch_mode0_extract3(hipStream_t st, int nint, int mF, const double* r, double* g0, double* zero_out) {
   const int n = 3 * nint;
@@ -947,6 +1056,13 @@ void launch_uzawa_update3(hipStream_t st, int nc, int mF, const int* cell_dofs, 
                           const double* vol, const double* lam, double eps_inv, double* p0, double* part, int nb) {
   hipLaunchKernelGGL(k_uzawa_update3, dim3(nb), dim3(256), 0, st, nc, mF, cell_dofs, cdiv, vol, lam, eps_inv, p0,
                      part);
+}
+
+void launch_f32_blocks_noal(hipStream_t st, int nc, int mF, const double* S, const double* cdiv, const double* vol,
+                            double al, float* out) {
+  const long n = (long)nc * 144 * mF * mF;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_f32_blocks_noal, dim3(blocks(n, 256)), dim3(256), 0, st, nc, mF, S, cdiv, vol, al, out);
 }
 
 void launch_f32_copy(hipStream_t st, long n, const double* in, float* out) {

@@ -80,7 +80,13 @@ struct Level3View {
   const int* cell_dofs;  // [nc][4] interior face id or -1
   const int* fcell;      // [nint][2] cells of each interior face
   const int* floc;       // [nint][2] local face index in those cells
-  const TS* S;           // [nc][nK][nK] symmetric cell blocks of A^eps
+  const TS* S;           // [nc][nK][nK] symmetric cell blocks of A^eps, or of A
+                         // (al > 0: the AL term is added apart, in FP64)
+  // AL term eps^-1 |K|^-1 d d^T applied apart when al > 0: d_i = cdiv[4K+i]
+  // on the mode-0 normal unknown of local face i
+  double al;
+  const double* cdiv;    // [nc][4]
+  const double* vol;     // [nc]
 };
 
 enum { TET_CONDENSE = 0, TET_LOAD = 1, TET_RECOVER = 2 };
@@ -121,9 +127,10 @@ void launch_patch_inverse3(hipStream_t st, Level3View<double> L, const int* pf_p
                            double* ws, double* pinv, int* status);
 // Block Gauss-Seidel on the patches [p0, p1) of one colour:
 // x_s += A_ss^-1 (b - A x)_s, a workgroup per patch.
-template <typename TS>
+// (TS: storage of the cell blocks, TP: of the patch inverses)
+template <typename TS, typename TP>
 void launch_patch_gs3(hipStream_t st, Level3View<TS> L, const int* pf_ptr, const int* pf, const int* pc_ptr,
-                      const int* pc, const long* poff, const TS* pinv, int p0, int p1, double* x,
+                      const int* pc, const long* poff, const TP* pinv, int p0, int p1, double* x,
                       const double* b);
 // Lowest-order part of an order-k skeleton vector (mode 0 of each face
 // component) and its injection.
@@ -138,5 +145,8 @@ void launch_uzawa_update3(hipStream_t st, int nc, int mF, const int* cell_dofs, 
                           const double* vol, const double* lam, double eps_inv, double* p0, double* part, int nb);
 // out[i] = (float) in[i]
 void launch_f32_copy(hipStream_t st, long n, const double* in, float* out);
+// FP32 copy of cell blocks without their AL term: out = S - al |K|^-1 d d^T
+void launch_f32_blocks_noal(hipStream_t st, int nc, int mF, const double* S, const double* cdiv, const double* vol,
+                            double al, float* out);
 
 }  // namespace hdgmg

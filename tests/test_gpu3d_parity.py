@@ -145,3 +145,24 @@ def test_divergence_free_gpu_solution():
     u, p, state, info, st = s.solve(dev(f))
     assert st == 0
     assert info["div_l2"] <= 1e-8 * float(torch.linalg.norm(u))
+
+
+@pytest.mark.parametrize("k,prec", [(1, 1), (2, 1), (3, 1), (3, 3)])
+def test_mixed_precision_vcycle(k, prec):
+    """FP32 storage of the V-cycle's operators (cell blocks without their AL
+    term, which is added apart in FP64; patch inverses; CR levels; transfers;
+    coarsest inverse; precision 3 keeps the order-k patch inverses FP64)
+    inside the FP64 flexible CG: the same relative
+    residual 1e-8 on the FP64 operator within two more iterations than the
+    FP64 V-cycle, and the two solutions agree to 1e-6."""
+    _note(f"3D mixed-precision V-cycle, k={k}, precision {prec}, 8^3 Kuhn cubes")
+    c, t = synth.kuhn_cube(2)
+    s64 = gpu(c, t, 2, k, 1.0, 1.0, 1e3)
+    s32 = gpu(c, t, 2, k, 1.0, 1.0, 1e3, vcycle_precision=prec)
+    b = dev(synth.uniform_pm1(6, 0, (s64.n_skel,)))
+    x64, its64, r64, st64 = s64.inner_solve(b)
+    x32, its32, r32, st32 = s32.inner_solve(b)
+    _note(f"  its FP64 {its64}, FP32 storage {its32}")
+    assert st64 == 0 and st32 == 0
+    assert its32 <= its64 + 2
+    assert rel(host(x32), host(x64)) <= 1e-6
