@@ -503,6 +503,7 @@ def main():
                     help="parameter sweeps instead of the bench line: the 256x256 generalized Stokes "
                          "workload over k, beta, gamma and V-cycle precision, and the cavity over Re; "
                          "one JSON line per case, then a summary line")
+    ap.add_argument("--profile-solves", type=int, default=2)
     ap.add_argument("--profile-run", action="store_true",
                     help="counter-collection run: a 1 GiB device copy (calibration of the HBM "
                          "counters) then two FP64 inner solves of the cube workload; prints a summary only")
@@ -529,9 +530,11 @@ def main():
         sweep(hd, synth, torch, np, c, t, a)
         return
     if a.profile_run:
+        # calibration: an elementwise kernel reading exactly 1 GiB and
+        # writing exactly 1 GiB
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.add(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
         c3, t3 = synth.kuhn_cube(4)
@@ -539,7 +542,7 @@ def main():
         s.assemble()
         g = torch.ones(s.n_skel, dtype=torch.float64, device="cuda")
         x = torch.empty_like(g)
-        for _ in range(2):
+        for _ in range(a.profile_solves):
             _, its, rel, st = s.inner_solve(g, x)
         torch.cuda.synchronize()
         print(json.dumps({"profile_run": True, "n_skel": s.n_skel, "iterations": its}))

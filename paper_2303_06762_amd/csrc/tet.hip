@@ -198,6 +198,8 @@ __global__ void __launch_bounds__(NT) k_tet_local(TetCells E, int mode, int c0, 
   __shared__ int piv;
   __shared__ double pinv_s;
   __shared__ double lamK[12 * MF3MAX];
+  __shared__ double red_v[NT];
+  __shared__ int red_i[NT];
   const int cell = c0 + blockIdx.x;
   const int tid = threadIdx.x;
   const TetTables& T = *E.T;
@@ -455,20 +457,33 @@ __global__ void __launch_bounds__(NT) k_tet_local(TetCells E, int mode, int c0, 
       }
   }
   __syncthreads();
-  // Gauss-Jordan elimination with partial pivoting
+  // Gauss-Jordan elimination with partial pivoting (pivot: block-wide
+  // argmax of |column j| below the diagonal, first index on ties)
   for (int j = 0; j < nkkt; ++j) {
-    if (tid == 0) {
-      int p = j;
-      double best = fabs(KA[(long)j * ldk + j]);
-      for (int i = j + 1; i < nkkt; ++i) {
-        const double v = fabs(KA[(long)i * ldk + j]);
-        if (v > best) {
-          best = v;
-          p = i;
+    {
+      double v = -1.0;
+      int idx = j;
+      for (int i = j + tid; i < nkkt; i += NT) {
+        const double a = fabs(KA[(long)i * ldk + j]);
+        if (a > v) {
+          v = a;
+          idx = i;
         }
       }
-      piv = p;
-      if (!(best > 0.0)) atomicOr(status, 2);
+      red_v[tid] = v;
+      red_i[tid] = idx;
+      __syncthreads();
+      for (int w = NT / 2; w > 0; w >>= 1) {
+        if (tid < w && (red_v[tid + w] > red_v[tid] || (red_v[tid + w] == red_v[tid] && red_i[tid + w] < red_i[tid]))) {
+          red_v[tid] = red_v[tid + w];
+          red_i[tid] = red_i[tid + w];
+        }
+        __syncthreads();
+      }
+      if (tid == 0) {
+        piv = red_i[0];
+        if (!(red_v[0] > 0.0)) atomicOr(status, 2);
+      }
     }
     __syncthreads();
     const int p = piv;
@@ -726,7 +741,6 @@ __global__ void __launch_bounds__(NT) k_patch_inverse3(Level3View<double> L, con
                                                        int p0, int ns_max, double* ws, double* pinv,
                                                        int* status) {
   __shared__ int slot[PMAX_CELLS][4];
-  __shared__ int piv;
   __shared__ double pv;
   __shared__ double fct[PMAX_FACES * 3 * MF3MAX];
   const int p = p0 + blockIdx.x, tid = threadIdx.x;
@@ -760,39 +774,22 @@ __global__ void __launch_bounds__(NT) k_patch_inverse3(Level3View<double> L, con
     }
     __syncthreads();
   }
+  // A_ss is symmetric positive definite: Gauss-Jordan without pivoting
   for (int j = 0; j < ns; ++j) {
     if (tid == 0) {
-      int q = j;
-      double best = fabs(A[(long)j * w + j]);
-      for (int i = j + 1; i < ns; ++i)
-        if (fabs(A[(long)i * w + j]) > best) {
-          best = fabs(A[(long)i * w + j]);
-          q = i;
-        }
-      piv = q;
-      pv = best > 0.0 ? 1.0 : 0.0;
-      if (!(best > 0.0)) atomicOr(status, 2);
-    }
-    __syncthreads();
-    const int q = piv;
-    if (q != j)
-      for (int c = tid; c < w; c += NT) {
-        const double t = A[(long)j * w + c];
-        A[(long)j * w + c] = A[(long)q * w + c];
-        A[(long)q * w + c] = t;
-      }
-    __syncthreads();
-    if (tid == 0) {
       const double v = A[(long)j * w + j];
-      pv = v != 0.0 ? 1.0 / v : 0.0;
+      if (!(v > 0.0)) atomicOr(status, 2);
+      pv = v > 0.0 ? 1.0 / v : 0.0;
     }
     __syncthreads();
-    for (int c = tid; c < w; c += NT) A[(long)j * w + c] *= pv;
+    // row j is zero left of column j and right of column ns + j
+    const int cw = ns + 1;
+    for (int c = j + tid; c <= ns + j; c += NT) A[(long)j * w + c] *= pv;
     for (int i = tid; i < ns; i += NT) fct[i] = i == j ? 0.0 : A[(long)i * w + j];
     __syncthreads();
-    for (long e = tid; e < (long)ns * w; e += NT) {
-      const int i = (int)(e / w), c = (int)(e % w);
-      if (i != j) A[e] -= fct[i] * A[(long)j * w + c];
+    for (long e = tid; e < (long)ns * cw; e += NT) {
+      const int i = (int)(e / cw), c = j + (int)(e % cw);
+      if (i != j) A[(long)i * w + c] -= fct[i] * A[(long)j * w + c];
     }
     __syncthreads();
   }
