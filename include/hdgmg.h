@@ -208,17 +208,20 @@ hdgmg_status hdgmg_assemble(hdgmg_ctx* ctx);
 
 /* Full solve (stOpEq-ALU): condensed load from f, AL-Uzawa outer loop with
  * a flexible-CG inner solve preconditioned by MG_hp (Alg. 2), then local
- * recovery.
- *   f_qp   device, [n_cells][n_q][2] source at the data points
- *   u_qp   device, [n_cells][n_q][2] velocity at the data points (output)
- *   p_qp   device, [n_cells][n_q] pressure, mean zero (output)
- *   state  device or NULL, [N_skel + n_cells]: skeleton coefficients then the
- *          piecewise-constant pressure (output)
- *   info   host or NULL (output)
+ * recovery, for nrhs >= 1 right-hand sides one after the other on this
+ * context (arrays stacked over the right-hand sides; hdgmg_solve_batch
+ * spreads a batch over several contexts and streams instead).
+ *   f_qp   device, [nrhs][n_cells][n_q][d] source at the data points
+ *          (d = 2 on triangles, 3 on tetrahedra)
+ *   u_qp   device, [nrhs][n_cells][n_q][d] velocity at the data points (output)
+ *   p_qp   device, [nrhs][n_cells][n_q] pressure, mean zero (output)
+ *   state  device or NULL, [nrhs][N_skel + n_cells]: skeleton coefficients
+ *          then the piecewise-constant pressure (output)
+ *   info   host or NULL, [nrhs] (output)
  * Returns OK, NOT_CONVERGED (an inner solve hit max_it or Uzawa hit
  * uzawa_max; outputs hold the last iterate), ESTATE, EBREAKDOWN, ENONFINITE,
  * EHIP. */
-hdgmg_status hdgmg_solve(hdgmg_ctx* ctx, const double* f_qp, double* u_qp,
+hdgmg_status hdgmg_solve(hdgmg_ctx* ctx, int nrhs, const double* f_qp, double* u_qp,
                          double* p_qp, double* state, hdgmg_info* info);
 
 /* Adjoint solve for a functional J(u_qp) of the velocity at the data points
@@ -227,6 +230,8 @@ hdgmg_status hdgmg_solve(hdgmg_ctx* ctx, const double* f_qp, double* u_qp,
  * nu-weighted lifting energy of each cell, and from its Picard-linearised
  * form of Sec. 4.2 at a fixed wind, whose convection form is nonsymmetric
  * and independent of the viscosity).
+ * For nrhs >= 1 right-hand sides one after the other (f_qp, state, gu_qp,
+ * gf_qp, adj_state and info stacked over them; gnu accumulates all).
  *   f_qp   device [n_cells][n_q][2], input: the forward source
  *   state  device [N_skel + n_cells], input: the forward state written by
  *          hdgmg_solve for f_qp (the forward solution is checkpointed as
@@ -254,7 +259,7 @@ hdgmg_status hdgmg_solve(hdgmg_ctx* ctx, const double* f_qp, double* u_qp,
  * forward local fields of gnu.  gf_qp must not alias the inputs.  Returns
  * as hdgmg_solve; outputs are undefined on a negative status.  ESTATE with a
  * wind on a context without opts.transpose. */
-hdgmg_status hdgmg_solve_adjoint(hdgmg_ctx* ctx, const double* f_qp, const double* state,
+hdgmg_status hdgmg_solve_adjoint(hdgmg_ctx* ctx, int nrhs, const double* f_qp, const double* state,
                                  const double* gu_qp, double* gf_qp, double* gnu,
                                  double* adj_state, hdgmg_info* info);
 
@@ -276,9 +281,10 @@ hdgmg_status hdgmg_solve_batch(hdgmg_ctx* const* ctxs, int nctx, int nrhs,
 
 /* The adjoint of a batch (hdgmg_solve_adjoint per right-hand side, spread
  * over the contexts as hdgmg_solve_batch): f_qp, states, gu_qp and gf_qp
- * stacked over the batch; gnu device [nctx][n_cells] or NULL, row c
- * ACCUMULATED by context c over its share (sum the rows for dJ/dnu of the
- * whole batch). */
+ * stacked over the batch; gnu device [n_cells] or NULL, ACCUMULATED with
+ * dJ/dnu summed over the whole batch (each context collects its share in a
+ * buffer of its own, added into gnu on the first context's stream at the
+ * end). */
 hdgmg_status hdgmg_solve_adjoint_batch(hdgmg_ctx* const* ctxs, int nctx, int nrhs,
                                        const double* f_qp, const double* states,
                                        const double* gu_qp, double* gf_qp,
@@ -339,6 +345,62 @@ hdgmg_status hdgmg_set_wind(hdgmg_ctx* ctx, const double* w_qp);
  * RT0-projected wind.  hdgmg_set_wind clears the Newton state.  Requires
  * opts.oseen = 1, opts.transpose = 0, k >= 1 and a wind (else ESTATE). */
 hdgmg_status hdgmg_set_newton(hdgmg_ctx* ctx, const double* state_prev);
+
+/* Alg. 3 (Sec. 4.2) in the library: a Stokes solve, Picard steps until
+ * ||u_n - u_{n-1}||_0 < eps_picard (or max_picard of them), then Newton
+ * steps until ||u_n - u_{n-1}||_0 <= max(newton_rtol ||u_n||_0, newton_atol)
+ * (or max_newton of them).  Each step after the first takes the previous
+ * velocity as the wind (hdgmg_set_wind), a Newton step also its state
+ * (hdgmg_set_newton), re-assembles, and starts from the previous skeleton
+ * vector (a Newton step's AL-Uzawa loop from the previous pressure); norms
+ * are L^2 norms by the data rule, computed on the device.  The context's
+ * Dirichlet data (hdgmg_set_dirichlet) apply to every step.
+ *   f_qp   device [n_cells][n_q][2] body force
+ *   a      host, the parameters below
+ *   u_qp, p_qp, state  device (outputs, as hdgmg_solve): the last step's
+ *          solution; during step_fn they hold the current step's
+ *   info   host or NULL: per step kind (0 Stokes, 1 Picard, 2 Newton),
+ *          ||u_n - u_{n-1}||_0 (-1 for the first), status, Uzawa steps and
+ *          summed inner iterations
+ *   step_fn, step_ctx  NULL, or called on the calling thread after every
+ *          step with the step's index, kind, status, norm and hdgmg_info
+ *          (the outputs then hold that step's solution; the stream is
+ *          synchronised)
+ * Requires opts.oseen = 1, opts.transpose = 0 (ESTATE), Newton k >= 1.
+ * Allocates two buffers (previous velocity and state) at the first call.
+ * Returns the largest status of the steps (NOT_CONVERGED if any inner
+ * solve did not converge), or the first negative one. */
+#define HDGMG_MAX_ALG3 128
+typedef struct {
+  double eps_picard;       /* Picard -> Newton switch (1e-4 in Sec. 5)      */
+  double newton_rtol;      /* relative Newton stop (1e-8)                   */
+  double newton_atol;      /* absolute Newton stop (1e-10)                  */
+  int max_picard;          /* Picard step cap                                */
+  int max_newton;          /* Newton step cap (0: Picard only)               */
+} hdgmg_alg3_opts;
+typedef struct {
+  int n_steps;
+  int kind[HDGMG_MAX_ALG3];
+  double du[HDGMG_MAX_ALG3];
+  int status[HDGMG_MAX_ALG3];
+  int uzawa_steps[HDGMG_MAX_ALG3];
+  int its[HDGMG_MAX_ALG3];
+  double t_total;          /* host wall time of the call, seconds            */
+} hdgmg_alg3_info;
+typedef void (*hdgmg_alg3_step_fn)(void* step_ctx, int step, int kind, int status, double du,
+                                   const hdgmg_info* info);
+hdgmg_status hdgmg_picard_newton(hdgmg_ctx* ctx, const double* f_qp, const hdgmg_alg3_opts* a, double* u_qp,
+                                 double* p_qp, double* state, hdgmg_alg3_info* info,
+                                 hdgmg_alg3_step_fn step_fn, void* step_ctx);
+
+/* Tangential Dirichlet data given as one constant velocity per boundary
+ * facet, g_b device [n_boundary_facets][2] (facet order, hdgmg_export what
+ * 3): the library sets uhat . t_F = g_b . t_F (mode 0; the exact facet L^2
+ * projection of a constant) and the higher modes to zero, then applies them
+ * as hdgmg_set_dirichlet does (the lid of a cavity: (1, 0) on the top
+ * facets, zero elsewhere).  NULL restores homogeneous data.  Allocates two
+ * small buffers at the first call. */
+hdgmg_status hdgmg_set_dirichlet_velocity(hdgmg_ctx* ctx, const double* g_b);
 
 /* Tangential Dirichlet data on the boundary facets (the lid of a cavity):
  * uhat_b device [n_boundary_facets][k+1], per boundary facet (in facet
@@ -412,6 +474,9 @@ hdgmg_status hdgmg_query(const hdgmg_ctx* ctx, int what, int level, int64_t* val
  *           [n_boundary_facets][2][2] (vertex v0 < v1 first: t_F points
  *           from the first to the second)
  *   what 4: data-rule weights times cell areas, w_q |K|, [n_cells][n_q]
+ *   what 5: the tangential boundary coefficients the last
+ *           hdgmg_set_dirichlet_velocity built, [n_boundary_facets][k+1]
+ *           (ESTATE before the first such call)
  * Local DOF order inside a block: (local facet i, component c, mode j) ->
  * (i*2 + c)*m + j, local facet i opposite the cell's i-th stored vertex.
  * `bytes` is the size of dst; EINVAL if too small. */

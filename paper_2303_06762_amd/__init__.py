@@ -44,6 +44,29 @@ class Info(ctypes.Structure):
                 ("div_l2", ctypes.c_double), ("t_solve", ctypes.c_double)]
 
 
+def _info_dict(info):
+    n = info.uzawa_steps
+    return dict(uzawa_steps=n, its=list(info.its[:n]), rel_res=list(info.rel_res[:n]),
+                dp_l2=list(info.dp_l2[:n]), div_l2=info.div_l2, t_solve=info.t_solve)
+
+
+MAX_ALG3 = 128
+
+
+class Alg3Opts(ctypes.Structure):
+    _fields_ = [("eps_picard", ctypes.c_double), ("newton_rtol", ctypes.c_double),
+                ("newton_atol", ctypes.c_double), ("max_picard", ctypes.c_int), ("max_newton", ctypes.c_int)]
+
+
+class Alg3Info(ctypes.Structure):
+    _fields_ = [("n_steps", ctypes.c_int), ("kind", ctypes.c_int * MAX_ALG3),
+                ("du", ctypes.c_double * MAX_ALG3), ("status", ctypes.c_int * MAX_ALG3),
+                ("uzawa_steps", ctypes.c_int * MAX_ALG3), ("its", ctypes.c_int * MAX_ALG3),
+                ("t_total", ctypes.c_double)]
+
+
+ALG3_STEP_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                ctypes.POINTER(Info))
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
@@ -82,7 +105,8 @@ class HdgmgError(RuntimeError):
 
 
 SYMBOLS = ["hdgmg_default_opts", "hdgmg_setup", "hdgmg_assemble", "hdgmg_solve",
-           "hdgmg_solve_adjoint", "hdgmg_solve_x0", "hdgmg_set_wind", "hdgmg_set_newton", "hdgmg_set_dirichlet", "hdgmg_postprocess",
+           "hdgmg_solve_adjoint", "hdgmg_solve_x0", "hdgmg_set_wind", "hdgmg_set_newton", "hdgmg_set_dirichlet",
+           "hdgmg_set_dirichlet_velocity", "hdgmg_picard_newton", "hdgmg_postprocess",
            "hdgmg_solve_batch", "hdgmg_solve_adjoint_batch",
            "hdgmg_rhs",
            "hdgmg_apply", "hdgmg_precondition", "hdgmg_inner_solve", "hdgmg_inner_solve_noalloc", "hdgmg_recover",
@@ -106,13 +130,16 @@ def lib():
     L.hdgmg_setup.restype = i32
     L.hdgmg_assemble.argtypes = [vp]
     L.hdgmg_assemble.restype = i32
-    L.hdgmg_solve.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(Info)]
+    L.hdgmg_solve.argtypes = [vp, i32, vp, vp, vp, vp, ctypes.POINTER(Info)]
     L.hdgmg_solve.restype = i32
-    L.hdgmg_solve_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(Info)]
+    L.hdgmg_solve_adjoint.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, ctypes.POINTER(Info)]
     L.hdgmg_solve_adjoint.restype = i32
+    L.hdgmg_picard_newton.argtypes = [vp, vp, ctypes.POINTER(Alg3Opts), vp, vp, vp, ctypes.POINTER(Alg3Info),
+                                      ALG3_STEP_FN, vp]
+    L.hdgmg_picard_newton.restype = i32
     L.hdgmg_solve_x0.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(Info)]
     L.hdgmg_solve_x0.restype = i32
-    for name in ("hdgmg_set_wind", "hdgmg_set_newton", "hdgmg_set_dirichlet"):
+    for name in ("hdgmg_set_wind", "hdgmg_set_newton", "hdgmg_set_dirichlet", "hdgmg_set_dirichlet_velocity"):
         getattr(L, name).argtypes = [vp, vp]
         getattr(L, name).restype = i32
     for name in ("hdgmg_rhs", "hdgmg_apply", "hdgmg_precondition"):
@@ -287,10 +314,7 @@ class Solver:
         pip = ctypes.c_void_p(None) if p_init is None else _ptr(p_init)
         st = self._check(lib().hdgmg_solve_x0(self._h, _ptr(f_qp), x0p, pip, _ptr(u), _ptr(p), _ptr(state),
                                               ctypes.byref(info)), allow=(0, 1))
-        n = info.uzawa_steps
-        d = dict(uzawa_steps=n, its=list(info.its[:n]), rel_res=list(info.rel_res[:n]),
-                 dp_l2=list(info.dp_l2[:n]), div_l2=info.div_l2, t_solve=info.t_solve)
-        return u, p, state, d, st
+        return u, p, state, _info_dict(info), st
 
     def solve_adjoint(self, f_qp, state, gu_qp, gnu=None, adj_state=None):
         """Adjoint of solve() for dJ/du_qp = gu_qp: returns (gf_qp, gnu,
@@ -303,13 +327,39 @@ class Solver:
         if adj_state is None:
             adj_state = self._vec(self.n_skel + self.n_cells)
         info = Info()
-        st = self._check(lib().hdgmg_solve_adjoint(self._h, _ptr(f_qp), _ptr(state), _ptr(gu_qp), _ptr(gf),
+        st = self._check(lib().hdgmg_solve_adjoint(self._h, 1, _ptr(f_qp), _ptr(state), _ptr(gu_qp), _ptr(gf),
                                                    _ptr(gnu), _ptr(adj_state), ctypes.byref(info)),
                          allow=(0, 1))
-        n = info.uzawa_steps
-        d = dict(uzawa_steps=n, its=list(info.its[:n]), rel_res=list(info.rel_res[:n]),
-                 dp_l2=list(info.dp_l2[:n]), div_l2=info.div_l2, t_solve=info.t_solve)
-        return gf, gnu, adj_state, d, st
+        return gf, gnu, adj_state, _info_dict(info), st
+
+    def solve_many(self, f_qp):
+        """hdgmg_solve over nrhs = f_qp.shape[0] sources stacked
+        [nrhs][n_cells][n_q][d]: returns (u, p, states, infos, status)."""
+        t = self.torch
+        n = f_qp.shape[0]
+        u = t.empty((n, self.n_cells, self.n_q, self.dim), dtype=t.float64, device="cuda")
+        p = t.empty((n, self.n_cells, self.n_q), dtype=t.float64, device="cuda")
+        states = t.zeros((n, self.n_skel + self.n_cells), dtype=t.float64, device="cuda")
+        infos = (Info * n)()
+        st = self._check(lib().hdgmg_solve(self._h, n, _ptr(f_qp.contiguous()), _ptr(u), _ptr(p), _ptr(states),
+                                           infos), allow=(0, 1))
+        return u, p, states, [_info_dict(i) for i in infos], st
+
+    def solve_adjoint_many(self, f_qp, states, gu_qp):
+        """hdgmg_solve_adjoint over nrhs = f_qp.shape[0] stacked forward
+        sources, states and dJ/du: returns (gf [nrhs][n_cells][n_q][d], gnu
+        [n_cells] summed over the right-hand sides, adj_states, infos,
+        status)."""
+        t = self.torch
+        n = f_qp.shape[0]
+        gf = t.empty((n, self.n_cells, self.n_q, self.dim), dtype=t.float64, device="cuda")
+        gnu = t.zeros(self.n_cells, dtype=t.float64, device="cuda")
+        adj = t.zeros((n, self.n_skel + self.n_cells), dtype=t.float64, device="cuda")
+        infos = (Info * n)()
+        st = self._check(lib().hdgmg_solve_adjoint(self._h, n, _ptr(f_qp.contiguous()), _ptr(states.contiguous()),
+                                                   _ptr(gu_qp.contiguous()), _ptr(gf), _ptr(gnu), _ptr(adj),
+                                                   infos), allow=(0, 1))
+        return gf, gnu, adj, [_info_dict(i) for i in infos], st
 
     def set_wind(self, w_qp):
         """Picard wind at the data points [n_cells][n_q][2] (None: no
@@ -347,17 +397,19 @@ class Solver:
         self._check(lib().hdgmg_export(self._h, 3, 0, _ptr(out), out.numel() * 8))
         return out[:nb]
 
-    def lid_data(self, top=1.0):
-        """uhat = (1, 0) on the boundary facets of the side y = top (mode 0
-        = (1, 0) . t_F), zero elsewhere: [n_boundary_facets][k+1]."""
-        t = self.torch
-        e = self.boundary_facets()
-        d = e[:, 1] - e[:, 0]
-        tx = d[:, 0] / t.linalg.norm(d, dim=1)
-        on = (e[:, 0, 1] - top).abs().lt(1e-12) & (e[:, 1, 1] - top).abs().lt(1e-12)
-        out = t.zeros((e.shape[0], self.k + 1), dtype=t.float64, device="cuda")
-        out[:, 0] = t.where(on, tx, t.zeros_like(tx))
-        return out
+    def set_dirichlet_velocity(self, g_b):
+        """hdgmg_set_dirichlet_velocity: tangential data from one constant
+        velocity per boundary facet (None: homogeneous)."""
+        self._check(lib().hdgmg_set_dirichlet_velocity(self._h, ctypes.c_void_p(None) if g_b is None
+                                                       else _ptr(g_b.contiguous())))
+
+    def dirichlet_data(self):
+        """The tangential boundary coefficients [n_boundary_facets][k+1] the
+        last set_dirichlet_velocity built (hdgmg_export 5)."""
+        nb = self.query(10)
+        out = self.torch.empty((max(nb, 1), self.k + 1), dtype=self.torch.float64, device="cuda")
+        self._check(lib().hdgmg_export(self._h, 5, 0, _ptr(out), out.numel() * 8))
+        return out[:nb]
 
     def timer(self, kernel_class, enable=True):
         """Enable/disable the live event timer of a kernel class (see hdgmg.h)."""
@@ -460,13 +512,13 @@ def solve_adjoint_batch(pool, f_qp, states, gu_qp):
     f_qp, states, gu_qp = (t_.detach().contiguous() for t_ in (f_qp, states, gu_qp))
     n = f_qp.shape[0]
     gf = torch.empty_like(f_qp)
-    gnu = torch.zeros((len(pool), s0.n_cells), dtype=torch.float64, device="cuda")
+    gnu = torch.zeros(s0.n_cells, dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
     st = lib().hdgmg_solve_adjoint_batch(_batch_handles(pool), len(pool), n, _ptr(f_qp), _ptr(states),
                                          _ptr(gu_qp), _ptr(gf), _ptr(gnu), None)
     if st < 0:
         raise _batch_error(pool, st)
-    return gf, gnu.sum(dim=0)
+    return gf, gnu
 
 
 def solver_pool(n, coords, cells, n_refine, k, beta, nu, gamma, **kw):
@@ -517,43 +569,29 @@ def picard(solver, f_qp, steps, dirichlet=None):
 
 def picard_newton(solver, f_qp, dirichlet=None, eps_picard=1e-4, newton_rtol=1e-8, newton_atol=1e-10,
                   max_picard=50, max_newton=20):
-    """Alg. 3 on an opts.oseen Solver: a Stokes solve, Picard steps until
-    ||u_n - u_{n-1}||_0 < eps_picard, then Newton steps until
-    ||u_n - u_{n-1}||_0 <= max(newton_rtol ||u_n||_0, newton_atol); every
-    step starts from the previous skeleton vector, and a Newton step's
-    AL-Uzawa loop from the previous pressure (the paper's loop on the
-    increments from zero).  Returns a list of dicts (kind, u, p, state,
-    info, status, du) per solve."""
+    """Alg. 3 on an opts.oseen Solver through hdgmg_picard_newton (the loop,
+    its norms and the Picard -> Newton switch run in the library): a Stokes
+    solve, Picard steps until ||u_n - u_{n-1}||_0 < eps_picard, then Newton
+    steps until ||u_n - u_{n-1}||_0 <= max(newton_rtol ||u_n||_0,
+    newton_atol).  Returns a list of dicts (kind, u, p, state, info, status,
+    du) per solve, the fields copied in the library's per-step callback."""
     torch = solver.torch
-    W = solver.data_weights()
-
-    def l2(d):
-        return float(torch.sqrt((W[..., None] * d * d).sum()))
-
     if dirichlet is not None:
         solver.set_dirichlet(dirichlet)
-    solver.set_wind(None)
-    solver.assemble()
+    u = torch.empty((solver.n_cells, solver.n_q, 2), dtype=torch.float64, device="cuda")
+    p = torch.empty((solver.n_cells, solver.n_q), dtype=torch.float64, device="cuda")
+    state = solver._vec(solver.n_skel + solver.n_cells)
+    kinds = ("stokes", "picard", "newton")
     out = []
-    kind, n_p, n_n = "stokes", 0, 0
-    x0 = p_init = None
-    while True:
-        u, p, state, info, st = solver.solve(f_qp, x0=x0, p_init=p_init if kind == "newton" else None)
-        du = None if not out else l2(u - out[-1]["u"])
-        out.append(dict(kind=kind, u=u, p=p, state=state, info=info, status=st, du=du))
-        if kind == "newton":
-            n_n += 1
-            if du <= max(newton_rtol * l2(u), newton_atol) or n_n >= max_newton:
-                break
-        elif kind == "picard":
-            n_p += 1
-            if du < eps_picard or n_p >= max_picard:
-                kind = "newton"
-        else:
-            kind = "picard"
-        solver.set_wind(u)
-        if kind == "newton":
-            solver.set_newton(state)
-        solver.assemble()
-        x0, p_init = state[:solver.n_skel], state[solver.n_skel:]
+
+    def step(_ctx, n, kind, st, du, info_p):
+        i = info_p.contents
+        out.append(dict(kind=kinds[kind], u=u.clone(), p=p.clone(), state=state.clone(), status=st,
+                        du=None if du < 0 else du, info=_info_dict(i)))
+
+    cb = ALG3_STEP_FN(step)
+    a = Alg3Opts(eps_picard, newton_rtol, newton_atol, max_picard, max_newton)
+    info = Alg3Info()
+    solver._check(lib().hdgmg_picard_newton(solver._h, _ptr(f_qp), ctypes.byref(a), _ptr(u), _ptr(p), _ptr(state),
+                                            ctypes.byref(info), cb, None), allow=(0, 1))
     return out

@@ -739,6 +739,41 @@ __device__ inline double block_sum(double v, double* sh) {
   return r;
 }
 
+// block partials of sum_{K,q} w_q |K| |a - b|^2 over [nc][nq][2] fields (b may be null)
+__global__ void k_wdiff2(QuadTables Q, const double* __restrict__ X, const int* __restrict__ cells, int nc,
+                         const double* __restrict__ a, const double* __restrict__ b, double* part) {
+  __shared__ double sh[TPB];
+  double s = 0.0;
+  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < (long)nc * Q.nq; t += (long)gridDim.x * blockDim.x) {
+    const long c = t / Q.nq;
+    const int q = (int)(t % Q.nq);
+    const int* v = cells + 3 * c;
+    const double ax = X[2 * v[1]] - X[2 * v[0]], ay = X[2 * v[1] + 1] - X[2 * v[0] + 1];
+    const double bx = X[2 * v[2]] - X[2 * v[0]], by = X[2 * v[2] + 1] - X[2 * v[0] + 1];
+    const double w = Q.wq[q] * 0.5 * fabs(ax * by - ay * bx);
+    const double d0 = a[2 * t] - (b ? b[2 * t] : 0.0), d1 = a[2 * t + 1] - (b ? b[2 * t + 1] : 0.0);
+    s += w * (d0 * d0 + d1 * d1);
+  }
+  const double r = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = r;
+}
+
+__global__ void k_axpy(long n, double a, const double* __restrict__ x, double* __restrict__ y) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) y[t] += a * x[t];
+}
+
+// tangential Dirichlet coefficients of constant boundary velocities:
+// uhat_b[f][0] = g_b[f] . t_F, higher modes 0 (the facet L2 projection of a
+// constant onto the orthonormal Legendre modes)
+__global__ void k_dirichlet_const(int nb, int m, const double* __restrict__ tb, const double* __restrict__ gb,
+                                  double* __restrict__ uhat) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)nb * m) return;
+  const int f = (int)(t / m), j = (int)(t % m);
+  uhat[t] = j == 0 ? gb[2 * f] * tb[2 * f] + gb[2 * f + 1] * tb[2 * f + 1] : 0.0;
+}
+
 __global__ void k_dot(long n, const double* __restrict__ x, const double* __restrict__ y, double* part) {
   __shared__ double sh[TPB];
   double s = 0.0;
@@ -1037,6 +1072,17 @@ void launch_mdot(hipStream_t st, long n, int nv, const double* V, long ld, const
 void launch_maxpy(hipStream_t st, long n, int nv, const double* V, long ld, const double* h, double sign, double* w) {
   if (nv > 0 && n > 0)
     hipLaunchKernelGGL(k_maxpy, dim3(std::min<long>(nblk(n), 4096)), dim3(TPB), 0, st, n, nv, V, ld, h, sign, w);
+}
+void launch_wdiff2(hipStream_t st, const QuadTables& Q, const double* X, const int* cells, int nc, const double* a,
+                   const double* b, double* part, int nblocks) {
+  hipLaunchKernelGGL(k_wdiff2, dim3(nblocks), dim3(TPB), 0, st, Q, X, cells, nc, a, b, part);
+}
+void launch_axpy(hipStream_t st, long n, double a, const double* x, double* y) {
+  if (n > 0) hipLaunchKernelGGL(k_axpy, dim3(nblk(n)), dim3(TPB), 0, st, n, a, x, y);
+}
+void launch_dirichlet_const(hipStream_t st, int nb, int m, const double* tb, const double* gb, double* uhat) {
+  const long n = (long)nb * m;
+  if (n > 0) hipLaunchKernelGGL(k_dirichlet_const, dim3(nblk(n)), dim3(TPB), 0, st, nb, m, tb, gb, uhat);
 }
 void launch_scale(hipStream_t st, long n, double a, const double* x, double* y) {
   if (n > 0) hipLaunchKernelGGL(k_scale, dim3(nblk(n)), dim3(TPB), 0, st, n, a, x, y);

@@ -145,6 +145,14 @@ void launch_mdot(hipStream_t st, long n, int nv, const double* V, long ld, const
 void launch_maxpy(hipStream_t st, long n, int nv, const double* V, long ld, const double* h, double sign, double* w);
 // y = a x
 void launch_scale(hipStream_t st, long n, double a, const double* x, double* y);
+// y += a x
+void launch_axpy(hipStream_t st, long n, double a, const double* x, double* y);
+// block partials of sum_{K,q} w_q |K| |a - b|^2 on [nc][nq][2] (b may be null);
+// reduce with launch_finalize(part, nblocks, 1, ...)
+void launch_wdiff2(hipStream_t st, const QuadTables& Q, const double* X, const int* cells, int nc, const double* a,
+                   const double* b, double* part, int nblocks);
+// uhat_b [nb][m] from constant velocities g_b [nb][2] and facet tangents tb [nb][2]
+void launch_dirichlet_const(hipStream_t st, int nb, int m, const double* tb, const double* gb, double* uhat);
 void launch_fcg_xr(hipStream_t st, long n, double* x, double* r, double* r_old, const double* p,
                    const double* q, const double* sc, double* part, int nblocks);
 void launch_fcg_p(hipStream_t st, long n, double* p, const double* z, const double* sc);

@@ -198,6 +198,11 @@ struct hdgmg_ctx {
   std::vector<int> bfacets;   // boundary facets in facet order
   int* cbf = nullptr;         // [n_cells][3] boundary facet number or -1
   double* bdl = nullptr;      // [n_cells][3][k+1] local boundary values
+  double* btan = nullptr;     // [n_boundary_facets][2] tangents t_F (first use of constant data)
+  double* bvals = nullptr;    // [n_boundary_facets][k+1] coefficients built from constant data
+  // Alg. 3 (hdgmg_picard_newton): previous velocity and state
+  double* a3_u = nullptr;
+  double* a3_state = nullptr;
   bool has_bd = false;
   // FGMRES basis: V [(restart+1)][N_skel], Z [restart][N_skel], scalars
   double *gm_V = nullptr, *gm_Z = nullptr, *gm_h = nullptr, *gm_y = nullptr, *gm_part = nullptr;
@@ -237,6 +242,7 @@ struct hdgmg_ctx {
   double* adj_f = nullptr;      // [n_cells][n_q][2] adjoint source values
   double* adj_p = nullptr;      // [n_cells][n_q] adjoint pressure
   double* adj_state = nullptr;  // [N_skel + n_cells]
+  double* adj_gnu = nullptr;    // [n_cells] this context's share of a batch's dJ/dnu
   double* ws = nullptr;
   size_t ws_bytes = 0;
   int* status = nullptr;
@@ -2249,6 +2255,113 @@ hdgmg_status hdgmg_set_dirichlet(hdgmg_ctx* ctx, const double* uhat_b) {
   return HDGMG_OK;
 }
 
+hdgmg_status hdgmg_set_dirichlet_velocity(hdgmg_ctx* ctx, const double* g_b) {
+  if (ctx && ctx->d3) return HDGMG_ESTATE;
+  if (!ctx) return HDGMG_EINVAL;
+  if (!g_b) return hdgmg_set_dirichlet(ctx, nullptr);
+  const int nb = (int)ctx->bfacets.size();
+  if (!ctx->btan) {
+    const Level& LF = ctx->lv[ctx->J - 1];
+    std::vector<double> t(2 * (size_t)std::max(nb, 1), 0.0);
+    for (int i = 0; i < nb; ++i) {
+      t[2 * i] = LF.tang[2 * ctx->bfacets[i]];
+      t[2 * i + 1] = LF.tang[2 * ctx->bfacets[i] + 1];
+    }
+    TRY(upload(ctx, &ctx->btan, t));
+    TRY(dalloc(ctx, &ctx->bvals, (size_t)std::max(nb, 1) * (ctx->k + 1)));
+  }
+  launch_dirichlet_const(ctx->st, nb, ctx->k + 1, ctx->btan, g_b, ctx->bvals);
+  HIPC(hipGetLastError());
+  return hdgmg_set_dirichlet(ctx, ctx->bvals);
+}
+
+// ||a - b||_0 over the data points (b may be null)
+static hdgmg_status wnorm(hdgmg_ctx* ctx, const double* a, const double* b, double* out) {
+  const DevLevel& KL = ctx->K;
+  launch_wdiff2(ctx->st, ctx->Q, KL.X, KL.cells, KL.nc, a, b, ctx->part, RED_BLOCKS);
+  launch_finalize(ctx->st, ctx->part, RED_BLOCKS, 1, ctx->sc, SC_BB);
+  double hs[SC_N];
+  HIPC(hipMemcpyAsync(hs, ctx->sc, sizeof(hs), hipMemcpyDeviceToHost, ctx->st));
+  HIPC(hipStreamSynchronize(ctx->st));
+  *out = std::sqrt(std::max(hs[SC_BB], 0.0));
+  return HDGMG_OK;
+}
+
+hdgmg_status hdgmg_picard_newton(hdgmg_ctx* ctx, const double* f_qp, const hdgmg_alg3_opts* a, double* u_qp,
+                                 double* p_qp, double* state, hdgmg_alg3_info* info, hdgmg_alg3_step_fn step_fn,
+                                 void* step_ctx) {
+  if (ctx && ctx->d3) return HDGMG_ESTATE;
+  if (!ctx || !f_qp || !a || !u_qp || !p_qp || !state) return HDGMG_EINVAL;
+  if (!ctx->opts.oseen || ctx->opts.transpose) {
+    ctx->err = "hdgmg_picard_newton needs a context with opts.oseen = 1, opts.transpose = 0";
+    return HDGMG_ESTATE;
+  }
+  if (a->max_picard < 0 || a->max_newton < 0 || a->max_picard + a->max_newton + 1 > HDGMG_MAX_ALG3 ||
+      (a->max_newton > 0 && ctx->k < 1)) {
+    ctx->err = "hdgmg_picard_newton: step caps out of range (Newton needs k >= 1)";
+    return HDGMG_EINVAL;
+  }
+  const auto t0 = std::chrono::steady_clock::now();
+  const DevLevel& KL = ctx->K;
+  const long nqd = (long)KL.nc * ctx->Q.nq, ns = KL.ndof + KL.nc;
+  if (!ctx->a3_u) {
+    TRY(dalloc(ctx, &ctx->a3_u, (size_t)nqd * 2));
+    TRY(dalloc(ctx, &ctx->a3_state, (size_t)ns));
+  }
+  if (info) std::memset(info, 0, sizeof(*info));
+  TRY(hdgmg_set_wind(ctx, nullptr));
+  TRY(hdgmg_assemble(ctx));
+  int kind = 0, n_p = 0, n_n = 0, step = 0;
+  hdgmg_status result = HDGMG_OK;
+  while (true) {
+    hdgmg_info inf;
+    const bool warm = step > 0;
+    hdgmg_status s = hdgmg_solve_x0(ctx, f_qp, warm ? ctx->a3_state : nullptr,
+                                    kind == 2 ? ctx->a3_state + KL.ndof : nullptr, u_qp, p_qp, state, &inf);
+    if (s < 0) return s;
+    result = std::max(result, s);
+    double du = -1.0, un = 0.0;
+    if (warm) TRY(wnorm(ctx, u_qp, ctx->a3_u, &du));
+    if (kind == 2) TRY(wnorm(ctx, u_qp, nullptr, &un));
+    if (info) {
+      info->n_steps = step + 1;
+      info->kind[step] = kind;
+      info->du[step] = du;
+      info->status[step] = s;
+      info->uzawa_steps[step] = inf.uzawa_steps;
+      for (int i = 0; i < inf.uzawa_steps; ++i) info->its[step] += inf.its[i];
+    }
+    if (step_fn) {
+      HIPC(hipStreamSynchronize(ctx->st));
+      step_fn(step_ctx, step, kind, s, du, &inf);
+    }
+    ++step;
+    bool done = false;
+    if (kind == 2) {
+      ++n_n;
+      done = du <= std::max(a->newton_rtol * un, a->newton_atol) || n_n >= a->max_newton;
+    } else if (kind == 1) {
+      ++n_p;
+      if (du < a->eps_picard || n_p >= a->max_picard) {
+        kind = 2;
+        done = a->max_newton == 0;
+      }
+    } else {
+      kind = a->max_picard > 0 ? 1 : 2;
+      done = a->max_picard == 0 && a->max_newton == 0;
+    }
+    if (done) break;
+    // the next step linearises at this one
+    launch_copy(ctx->st, nqd * 2, u_qp, ctx->a3_u);
+    launch_copy(ctx->st, ns, state, ctx->a3_state);
+    TRY(hdgmg_set_wind(ctx, ctx->a3_u));
+    if (kind == 2) TRY(hdgmg_set_newton(ctx, ctx->a3_state));
+    TRY(hdgmg_assemble(ctx));
+  }
+  if (info) info->t_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return result;
+}
+
 hdgmg_status hdgmg_recover(hdgmg_ctx* ctx, const double* f_qp, const double* state, double* u_qp,
                            double* p_qp) {
   if (ctx && ctx->d3) return f_qp && state && u_qp && p_qp ? d3_recover(ctx->d3, f_qp, state, u_qp, p_qp) : HDGMG_EINVAL;
@@ -2282,9 +2395,23 @@ hdgmg_status hdgmg_postprocess(hdgmg_ctx* ctx, const double* f_qp, const double*
   return HDGMG_OK;
 }
 
-hdgmg_status hdgmg_solve(hdgmg_ctx* ctx, const double* f_qp, double* u_qp, double* p_qp, double* state,
+hdgmg_status hdgmg_solve(hdgmg_ctx* ctx, int nrhs, const double* f_qp, double* u_qp, double* p_qp, double* state,
                          hdgmg_info* info) {
-  return hdgmg_solve_x0(ctx, f_qp, nullptr, nullptr, u_qp, p_qp, state, info);
+  if (!ctx || nrhs < 1 || !f_qp || !u_qp || !p_qp) return HDGMG_EINVAL;
+  int64_t nc = 0, nq = 0, ns = 0, dim = 2;
+  TRY(hdgmg_query(ctx, 0, 0, &nc));
+  TRY(hdgmg_query(ctx, 1, 0, &nq));
+  TRY(hdgmg_query(ctx, 2, 0, &ns));
+  TRY(hdgmg_query(ctx, 11, 0, &dim));
+  hdgmg_status result = HDGMG_OK;
+  for (int i = 0; i < nrhs; ++i) {
+    const long o = (long)i * nc * nq;
+    hdgmg_status s = hdgmg_solve_x0(ctx, f_qp + o * dim, nullptr, nullptr, u_qp + o * dim, p_qp + o,
+                                    state ? state + (long)i * (ns + nc) : nullptr, info ? info + i : nullptr);
+    if (s < 0) return s;
+    result = std::max(result, s);
+  }
+  return result;
 }
 
 hdgmg_status hdgmg_solve_x0(hdgmg_ctx* ctx, const double* f_qp, const double* x0, const double* p_init,
@@ -2368,14 +2495,12 @@ static hdgmg_status adjoint_buffers(hdgmg_ctx* ctx) {
   TRY(dalloc(ctx, &ctx->adj_f, (size_t)nqd * 2));
   TRY(dalloc(ctx, &ctx->adj_p, (size_t)nqd));
   TRY(dalloc(ctx, &ctx->adj_state, (size_t)(ctx->K.ndof + ctx->K.nc)));
+  TRY(dalloc(ctx, &ctx->adj_gnu, (size_t)ctx->K.nc));
   return HDGMG_OK;
 }
 
-hdgmg_status hdgmg_solve_adjoint(hdgmg_ctx* ctx, const double* f_qp, const double* state, const double* gu_qp,
-                                 double* gf_qp, double* gnu, double* adj_state, hdgmg_info* info) {
-  if (ctx && ctx->d3) {
-    return HDGMG_ESTATE;
-  }
+static hdgmg_status adjoint_one(hdgmg_ctx* ctx, const double* f_qp, const double* state, const double* gu_qp,
+                                double* gf_qp, double* gnu, double* adj_state, hdgmg_info* info) {
   if (!ctx || !f_qp || !state || !gu_qp || !gf_qp) return HDGMG_EINVAL;
   if (!ctx->assembled) {
     ctx->err = "hdgmg_solve_adjoint before hdgmg_assemble";
@@ -2395,7 +2520,7 @@ hdgmg_status hdgmg_solve_adjoint(hdgmg_ctx* ctx, const double* f_qp, const doubl
   // enter only the forward state's local fields in the viscosity gradient
   const bool bd = ctx->has_bd;
   ctx->has_bd = false;
-  hdgmg_status result = hdgmg_solve(ctx, ctx->adj_f, gf_qp, ctx->adj_p, ast, info);
+  hdgmg_status result = hdgmg_solve_x0(ctx, ctx->adj_f, nullptr, nullptr, gf_qp, ctx->adj_p, ast, info);
   ctx->has_bd = bd;
   if (result < 0) return result;
   // dJ/df = w_q |K| u_adj(x_q)
@@ -2408,14 +2533,30 @@ hdgmg_status hdgmg_solve_adjoint(hdgmg_ctx* ctx, const double* f_qp, const doubl
   return result;
 }
 
+hdgmg_status hdgmg_solve_adjoint(hdgmg_ctx* ctx, int nrhs, const double* f_qp, const double* state,
+                                 const double* gu_qp, double* gf_qp, double* gnu, double* adj_state,
+                                 hdgmg_info* info) {
+  if (ctx && ctx->d3) return HDGMG_ESTATE;
+  if (!ctx || nrhs < 1) return HDGMG_EINVAL;
+  const long nqd = (long)ctx->K.nc * ctx->Q.nq, ns = ctx->K.ndof + ctx->K.nc;
+  hdgmg_status result = HDGMG_OK;
+  for (int i = 0; i < nrhs; ++i) {
+    hdgmg_status s = adjoint_one(ctx, f_qp + i * nqd * 2, state + i * ns, gu_qp + i * nqd * 2, gf_qp + i * nqd * 2,
+                                 gnu, adj_state ? adj_state + i * ns : nullptr, info ? info + i : nullptr);
+    if (s < 0) return s;
+    result = std::max(result, s);
+  }
+  return result;
+}
+
 hdgmg_status hdgmg_solve_batch(hdgmg_ctx* const* ctxs, int nctx, int nrhs, const double* f_qp, double* u_qp,
                                double* p_qp, double* states, hdgmg_info* infos) {
   TRY(batch_check(ctxs, nctx, nrhs));
   if (nrhs > 0 && (!f_qp || !u_qp || !p_qp)) return HDGMG_EINVAL;
   const long nqd = (long)ctxs[0]->K.nc * ctxs[0]->Q.nq, ns = ctxs[0]->K.ndof + ctxs[0]->K.nc;
   return batch_run(ctxs, nctx, nrhs, [&](hdgmg_ctx* ctx, int i) {
-    return hdgmg_solve(ctx, f_qp + i * nqd * 2, u_qp + i * nqd * 2, p_qp + i * nqd, states ? states + i * ns : nullptr,
-                       infos ? infos + i : nullptr);
+    return hdgmg_solve_x0(ctx, f_qp + i * nqd * 2, nullptr, nullptr, u_qp + i * nqd * 2, p_qp + i * nqd,
+                          states ? states + i * ns : nullptr, infos ? infos + i : nullptr);
   });
 }
 
@@ -2430,13 +2571,20 @@ hdgmg_status hdgmg_solve_adjoint_batch(hdgmg_ctx* const* ctxs, int nctx, int nrh
     hdgmg_status s = adjoint_buffers(ctxs[c]);
     if (s != HDGMG_OK) return s;
   }
-  // each context accumulates into its own row of gnu (no two streams add
-  // into the same array)
-  return batch_run(ctxs, nctx, nrhs, [&](hdgmg_ctx* ctx, int i) {
-    const int c = i % nctx;
-    return hdgmg_solve_adjoint(ctx, f_qp + i * nqd * 2, states + i * ns, gu_qp + i * nqd * 2, gf_qp + i * nqd * 2,
-                               gnu ? gnu + c * nc : nullptr, nullptr, infos ? infos + i : nullptr);
+  // each context accumulates into a buffer of its own (no two streams add
+  // into the same array); the shares are summed into gnu at the end
+  if (gnu)
+    for (int c = 0; c < nctx; ++c) launch_fill(ctxs[c]->st, nc, 0.0, ctxs[c]->adj_gnu);
+  hdgmg_status result = batch_run(ctxs, nctx, nrhs, [&](hdgmg_ctx* ctx, int i) {
+    return adjoint_one(ctx, f_qp + i * nqd * 2, states + i * ns, gu_qp + i * nqd * 2, gf_qp + i * nqd * 2,
+                       gnu ? ctx->adj_gnu : nullptr, nullptr, infos ? infos + i : nullptr);
   });
+  if (result < 0 || !gnu || nrhs <= 0) return result;
+  hdgmg_ctx* ctx = ctxs[0];
+  for (int c = 0; c < nctx; ++c) launch_axpy(ctx->st, nc, 1.0, ctxs[c]->adj_gnu, gnu);
+  HIPC(hipGetLastError());
+  HIPC(hipStreamSynchronize(ctx->st));
+  return result;
 }
 
 hdgmg_status hdgmg_kernel_timer(hdgmg_ctx* ctx, int cls, int enable) {
@@ -2513,6 +2661,20 @@ hdgmg_status hdgmg_export(const hdgmg_ctx* cctx, int what, int level, void* dst,
     for (int c = 0; c < LF.nc; ++c)
       for (int q = 0; q < ctx->Q.nq; ++q) w[(size_t)c * ctx->Q.nq + q] = ctx->Q.wq[q] * LF.area[c];
     HIPC(hipMemcpyAsync(dst, w.data(), n * sizeof(double), hipMemcpyHostToDevice, ctx->st));
+    HIPC(hipStreamSynchronize(ctx->st));
+    return HDGMG_OK;
+  }
+  if (what == 5) {
+    if (!ctx->bvals) {
+      ctx->err = "hdgmg_export 5: no hdgmg_set_dirichlet_velocity data on this context";
+      return HDGMG_ESTATE;
+    }
+    n = ctx->bfacets.size() * (ctx->k + 1);
+    if (bytes < n * sizeof(double)) {
+      ctx->err = "hdgmg_export: destination too small";
+      return HDGMG_EINVAL;
+    }
+    if (n > 0) HIPC(hipMemcpyAsync(dst, ctx->bvals, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->st));
     HIPC(hipStreamSynchronize(ctx->st));
     return HDGMG_OK;
   }

@@ -99,6 +99,17 @@ def kuhn_cube(n):
     return coords, np.asarray(cells, dtype=np.int32)
 
 
+def lid_velocity(ends, top=1.0):
+    """Boundary data of the lid-driven cavity: one constant velocity per
+    boundary facet, (1, 0) on the facets whose two end points lie on the side
+    y = top, zero elsewhere.  ends: array [n_boundary_facets][2][2]."""
+    ends = np.asarray(ends)
+    on = (np.abs(ends[:, 0, 1] - top) < 1e-12) & (np.abs(ends[:, 1, 1] - top) < 1e-12)
+    g = np.zeros((ends.shape[0], 2))
+    g[on, 0] = 1.0
+    return g
+
+
 def source_uniform(seed, nrhs, n_cells, n_qp, dim=2, stream=0):
     """f at the data quadrature points, i.i.d. uniform[-1,1):
     array [nrhs][n_cells][n_qp][dim]."""

@@ -223,3 +223,37 @@ def test_native_batch_calls():
     for p_ in pool:
         p_.close()
     s.close()
+
+
+def test_nrhs_entry_points():
+    # hdgmg_solve and hdgmg_solve_adjoint with nrhs = 3 on one context
+    # against three single-source calls; the viscosity gradient of the
+    # nrhs call is the sum of the single calls'
+    import paper_2303_06762_amd as hd
+    c, t = synth.kuhn_square(4)
+    nr, k, beta, gamma = 1, 2, 1.0, 1e2
+    n_cells = 32 * 4 ** nr
+    nu = lognormal_nu(n_cells)
+    nq = (k + 2) ** 2
+    F = dev(synth.source_uniform(210, 3, n_cells, nq))
+    GU = dev(synth.source_uniform(310, 3, n_cells, nq))
+    _note("nrhs entry points: 3 sources on one context")
+    s = hd.Solver(c, t, nr, k, beta, nu, gamma)
+    s.assemble()
+    U, P, S, infos, st = s.solve_many(F)
+    assert st == 0
+    GF, GNU, ADJ, ainfos, st = s.solve_adjoint_many(F, S, GU)
+    assert st == 0
+    gnu1 = torch.zeros(n_cells, dtype=torch.float64, device="cuda")
+    for i in range(3):
+        u, p, st_, info, st = s.solve(F[i])
+        assert st == 0 and infos[i]["its"] == info["its"]
+        assert (U[i] - u).abs().max().item() <= 1e-12 * u.abs().max().item()
+        assert (P[i] - p).abs().max().item() <= 1e-12 * p.abs().max().item()
+        assert (S[i] - st_).abs().max().item() <= 1e-12 * st_.abs().max().item()
+        gf, _, adj, ainfo, st = s.solve_adjoint(F[i], st_, GU[i], gnu=gnu1)
+        assert st == 0 and ainfos[i]["its"] == ainfo["its"]
+        assert (GF[i] - gf).abs().max().item() <= 1e-12 * gf.abs().max().item()
+        assert (ADJ[i] - adj).abs().max().item() <= 1e-12 * adj.abs().max().item()
+    assert (GNU - gnu1).abs().max().item() <= 1e-12 * gnu1.abs().max().item()
+    s.close()
