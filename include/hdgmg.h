@@ -141,12 +141,39 @@ typedef struct {
   int rec_wide;            /* 1: every record-smoothed level uses the 32-bit
                               record form (otherwise only levels beyond
                               65535 interior facets); same results      */
+  int smoother;            /* patch smoother of the order-k relaxation and
+                              the lowest-order smoothing (Sec. 3.4.2):
+                              0 block Gauss-Seidel, colour by colour, the
+                              transposed sweep in reverse colour order;
+                              1 damped block Jacobi (eq. bjac): every patch
+                              corrected from the residual at the start of
+                              the sweep, damping 1 / (number of patch
+                              colours of the level) -- within one colour
+                              the patch projections sum to a projection --
+                              its own transpose.  Jacobi runs the
+                              launch-per-colour kernels on every level of a
+                              triangular mesh (the streaming, record and
+                              single-workgroup forms are Gauss-Seidel only) */
+  int additive;            /* 0: MG_hp of Alg. 2 (relaxation, lowest-order
+                              correction of the new residual, relaxation);
+                              1: its additive counterpart (Remark 3.4):
+                              m_relax forward then m_relax transposed sweeps
+                              from zero on r, plus Pi_0^k MG_h(Pi_k^0 r) of
+                              the same r                                   */
+  int patch_relax;         /* patches of the order-k relaxation: 0 the
+                              dimension's default (vertex patches on
+                              triangles, edge patches on tetrahedra),
+                              1 vertex patches, 2 edge patches (tetrahedra
+                              only: EINVAL on triangles)                   */
+  int patch_smooth;        /* patches of the lowest-order smoothing, the
+                              same codes                                   */
 } hdgmg_opts;
 
 /* Defaults: m_p = m_h = 1, V-cycle, growth 2, rtol 1e-8, atol 1e-10,
  * max_it 500, uzawa_max 50, uzawa_tol 1e-10, coarse_dofs 2048,
  * stream_dofs 65536, vcycle_precision 0, oseen 0, restart 50, transpose 0,
- * coarse_dense 1, rec_wide 0. */
+ * coarse_dense 1, rec_wide 0, smoother 0, additive 0, patch_relax 0,
+ * patch_smooth 0. */
 void hdgmg_default_opts(hdgmg_opts* opts);
 
 #define HDGMG_MAX_UZAWA 64

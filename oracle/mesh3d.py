@@ -127,6 +127,35 @@ class Level3:
         return col
 
 
+    def vertex_patches(self):
+        """For each vertex, the interior faces containing it (sorted face ids)."""
+        out = [[] for _ in range(len(self.coords))]
+        for F in np.where(self.interior)[0]:
+            for v in self.faces[F]:
+                out[int(v)].append(int(F))
+        return [sorted(x) for x in out]
+
+    def vertex_colours(self, patches):
+        """Greedy colouring of the vertices with a non-empty patch, in vertex
+        order: each takes the smallest colour not used by an earlier such
+        vertex sharing a cell with it.  Vertices with an empty patch get -1."""
+        nv = len(self.coords)
+        cells_of = [[] for _ in range(nv)]
+        for K in range(self.n_cells):
+            for v in self.cells[K]:
+                cells_of[int(v)].append(K)
+        col = -np.ones(nv, dtype=np.int64)
+        for v in range(nv):
+            if not patches[v]:
+                continue
+            used = {int(col[w]) for K in cells_of[v] for w in self.cells[K] if col[w] >= 0}
+            c = 0
+            while c in used:
+                c += 1
+            col[v] = c
+        return col
+
+
 def refine(coords, cells):
     """Bey's red refinement with the numbering above: (coords, cells, parent)."""
     lvl = Level3(coords, cells)

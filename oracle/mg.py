@@ -23,10 +23,17 @@ from . import cr
 
 
 class PatchGS:
-    """Vertex-patch block Gauss-Seidel on a level with m modes per component."""
+    """Vertex-patch block Gauss-Seidel on a level with m modes per component;
+    with smoother="jacobi" the damped block Jacobi smoother (eq. bjac)
+    instead: x += s sum_s E_s (A_ss)^-1 E_s^T (b - A x), every patch from
+    the same residual, s = 1 / (number of colours) (within one colour the
+    patch projections are A-orthogonal, so their sum is a projection and
+    the sum over all patches is bounded by the colour count); it is its own
+    transpose."""
 
-    def __init__(self, A, lv, m):
+    def __init__(self, A, lv, m, smoother="gs"):
         self.A = A.tocsr()
+        self.jacobi = smoother == "jacobi"
         col = lv.vertex_colours()
         vf = lv.vertex_facets()
         self.colours = []
@@ -42,13 +49,26 @@ class PatchGS:
                 Ass = rows[:, d].toarray()
                 pats.append((d, rows, np.linalg.inv(Ass)))
             self.colours.append(pats)
+        self.damp = 1.0 / len(self.colours)
+
+    def _jacobi(self, x, b):
+        r = b - self.A @ x
+        dx = np.zeros_like(x)
+        for pats in self.colours:
+            for d, rows, Ainv in pats:
+                dx[d] += Ainv @ r[d]
+        x += self.damp * dx
 
     def forward(self, x, b):
+        if self.jacobi:
+            return self._jacobi(x, b)
         for pats in self.colours:
             for d, rows, Ainv in pats:
                 x[d] += Ainv @ (b[d] - rows @ x)
 
     def backward(self, x, b):
+        if self.jacobi:
+            return self._jacobi(x, b)
         for pats in reversed(self.colours):
             for d, rows, Ainv in pats:
                 x[d] += Ainv @ (b[d] - rows @ x)
@@ -128,7 +148,7 @@ def stabilised_transfer(Af, Iavg, tdofs):
 class Hierarchy:
     """Lowest-order levels 1..J with transfers and smoothers."""
 
-    def __init__(self, levels, nu_fine, beta, eps_inv, harmonic=True):
+    def __init__(self, levels, nu_fine, beta, eps_inv, harmonic=True, smoother="gs"):
         self.levels = levels
         J = len(levels)
         nus = [None] * J
@@ -138,7 +158,7 @@ class Hierarchy:
             nus[l - 1] = nus[l].reshape(-1, 4).mean(axis=1)
         self.nus = nus
         self.A = [cr.assemble(lv, nus[l], beta, eps_inv) for l, lv in enumerate(levels)]
-        self.smooth = [None] + [PatchGS(self.A[l], levels[l], 1) for l in range(1, J)]
+        self.smooth = [None] + [PatchGS(self.A[l], levels[l], 1, smoother) for l in range(1, J)]
         self.P = [None]
         for l in range(1, J):
             Iavg = averaging(levels[l - 1], levels[l])
@@ -168,19 +188,33 @@ class Hierarchy:
 
 
 class HPMG:
-    """Alg. 2 with zero initial guess: the preconditioner z = MG_hp(r)."""
+    """Alg. 2 with zero initial guess: the preconditioner z = MG_hp(r).
 
-    def __init__(self, Ak, lv, k, hier, m_p=1, m_h=1, q=1, growth=2):
+    additive=True: the additive (parallel) counterpart of Remark 3.4 -- the
+    relaxation (m_p forward then m_p transposed sweeps from zero on r) plus
+    the lowest-order correction Pi_0^k MG_h(Pi_k^0 r), both from the same r."""
+
+    def __init__(self, Ak, lv, k, hier, m_p=1, m_h=1, q=1, growth=2, smoother="gs", additive=False):
         self.Ak, self.k, self.hier = Ak.tocsr(), k, hier
         self.m_p, self.m_h, self.q, self.growth = m_p, m_h, q, growth
+        self.additive = additive
         m = k + 1
         self.mode0 = np.array([(f * 2 + c) * m for f in range(lv.n_int) for c in range(2)])
-        self.relax = PatchGS(self.Ak, lv, m) if k > 0 else None
+        self.relax = PatchGS(self.Ak, lv, m, smoother) if k > 0 else None
 
     def __call__(self, g):
         J = len(self.hier.levels) - 1
         if self.k == 0:
             return self.hier.mg_h(J, g, np.zeros_like(g), self.m_h, self.q, self.growth)
+        if self.additive:
+            x = np.zeros_like(g)
+            for _ in range(self.m_p):
+                self.relax.forward(x, g)
+            for _ in range(self.m_p):
+                self.relax.backward(x, g)
+            x[self.mode0] += self.hier.mg_h(J, g[self.mode0], np.zeros(len(self.mode0)), self.m_h,
+                                            self.q, self.growth)
+            return x
         x = np.zeros_like(g)
         for _ in range(self.m_p):
             self.relax.forward(x, g)

@@ -25,12 +25,21 @@ from . import cr3d
 
 
 class EdgePatchGS:
-    """Edge-patch block Gauss-Seidel on a level with m modes per component."""
+    """Edge-patch block Gauss-Seidel on a level with m modes per component;
+    smoother="jacobi": the damped block Jacobi smoother (eq. bjac) with
+    damping 1 / (number of colours), as mg.PatchGS; patch="vertex": vertex
+    patches (every interior face containing the vertex, greedy vertex
+    colouring) instead of edge patches."""
 
-    def __init__(self, A, lv, m):
+    def __init__(self, A, lv, m, smoother="gs", patch="edge"):
         self.A = A.tocsr()
-        pats_of = lv.edge_patches()
-        col = lv.edge_colours(pats_of)
+        self.jacobi = smoother == "jacobi"
+        if patch == "vertex":
+            pats_of = lv.vertex_patches()
+            col = lv.vertex_colours(pats_of)
+        else:
+            pats_of = lv.edge_patches()
+            col = lv.edge_colours(pats_of)
         self.colours = []
         for c in range(int(col.max()) + 1):
             pats = []
@@ -42,13 +51,26 @@ class EdgePatchGS:
                 Ass = rows[:, d].toarray()
                 pats.append((d, rows, np.linalg.inv(Ass)))
             self.colours.append(pats)
+        self.damp = 1.0 / len(self.colours)
+
+    def _jacobi(self, x, b):
+        r = b - self.A @ x
+        dx = np.zeros_like(x)
+        for pats in self.colours:
+            for d, rows, Ainv in pats:
+                dx[d] += Ainv @ r[d]
+        x += self.damp * dx
 
     def forward(self, x, b):
+        if self.jacobi:
+            return self._jacobi(x, b)
         for pats in self.colours:
             for d, rows, Ainv in pats:
                 x[d] += Ainv @ (b[d] - rows @ x)
 
     def backward(self, x, b):
+        if self.jacobi:
+            return self._jacobi(x, b)
         for pats in reversed(self.colours):
             for d, rows, Ainv in pats:
                 x[d] += Ainv @ (b[d] - rows @ x)
@@ -126,7 +148,7 @@ def stabilised_transfer(Af, Iavg, tdofs):
 class Hierarchy3:
     """Lowest-order levels 1..J on tetrahedra with transfers and smoothers."""
 
-    def __init__(self, levels, nu_fine, beta, eps_inv, harmonic=True):
+    def __init__(self, levels, nu_fine, beta, eps_inv, harmonic=True, smoother="gs", patch="edge"):
         self.levels = levels
         J = len(levels)
         nus = [None] * J
@@ -135,7 +157,7 @@ class Hierarchy3:
             nus[l - 1] = nus[l].reshape(-1, 8).mean(axis=1)
         self.nus = nus
         self.A = [cr3d.assemble(lv, nus[l], beta, eps_inv) for l, lv in enumerate(levels)]
-        self.smooth = [None] + [EdgePatchGS(self.A[l], levels[l], 1) for l in range(1, J)]
+        self.smooth = [None] + [EdgePatchGS(self.A[l], levels[l], 1, smoother, patch) for l in range(1, J)]
         self.P = [None]
         for l in range(1, J):
             Iavg = averaging(levels[l - 1], levels[l])
@@ -167,17 +189,29 @@ class Hierarchy3:
 class HPMG3:
     """Alg. 2 with zero initial guess on tetrahedra: z = MG_hp(r)."""
 
-    def __init__(self, Ak, lv, k, hier, m_p=2, m_h=2, q=1, growth=2):
+    def __init__(self, Ak, lv, k, hier, m_p=2, m_h=2, q=1, growth=2, smoother="gs", additive=False,
+                 patch="edge"):
         self.Ak, self.k, self.hier = Ak.tocsr(), k, hier
         self.m_p, self.m_h, self.q, self.growth = m_p, m_h, q, growth
+        self.additive = additive
         mF = (k + 1) * (k + 2) // 2
         self.mode0 = np.array([(f * 3 + c) * mF for f in range(lv.n_int) for c in range(3)])
-        self.relax = EdgePatchGS(self.Ak, lv, mF) if k > 0 else None
+        self.relax = EdgePatchGS(self.Ak, lv, mF, smoother, patch) if k > 0 else None
 
     def __call__(self, g):
         J = len(self.hier.levels) - 1
         if self.k == 0:
             return self.hier.mg_h(J, g, np.zeros_like(g), self.m_h, self.q, self.growth)
+        if self.additive:
+            # additive counterpart (Remark 3.4), as mg.HPMG
+            x = np.zeros_like(g)
+            for _ in range(self.m_p):
+                self.relax.forward(x, g)
+            for _ in range(self.m_p):
+                self.relax.backward(x, g)
+            x[self.mode0] += self.hier.mg_h(J, g[self.mode0], np.zeros(len(self.mode0)), self.m_h,
+                                            self.q, self.growth)
+            return x
         x = np.zeros_like(g)
         for _ in range(self.m_p):
             self.relax.forward(x, g)

@@ -314,7 +314,7 @@ class OseenHierarchy(mg.Hierarchy):
     """Lowest-order levels with the convection of the RT0-projected wind
     (flux: facet fluxes of the wind on the finest level; None: Stokes)."""
 
-    def __init__(self, levels, nu_fine, beta, eps_inv, flux=None, harmonic=True, transpose=False):
+    def __init__(self, levels, nu_fine, beta, eps_inv, flux=None, harmonic=True, transpose=False, smoother="gs"):
         self.levels = levels
         J = len(levels)
         nus = [None] * J
@@ -333,7 +333,7 @@ class OseenHierarchy(mg.Hierarchy):
             winds = None if flux is None else rt0_winds(lv, fluxes[l])
             pr = OseenProblem(lv, 0, nus[l], beta, eps_inv, winds, transpose=transpose)
             self.A.append(pr.matrix_Aeps().tocsr())
-        self.smooth = [None] + [mg.PatchGS(self.A[l], levels[l], 1) for l in range(1, J)]
+        self.smooth = [None] + [mg.PatchGS(self.A[l], levels[l], 1, smoother) for l in range(1, J)]
         self.P, self.R = [None], [None]
         for l in range(1, J):
             Iavg = mg.averaging(levels[l - 1], levels[l])
@@ -425,7 +425,7 @@ class OseenSetup:
     Oseen hierarchy."""
 
     def __init__(self, levels, k, nu, beta, gamma, winds=None, dirichlet=None, m_p=1, m_h=1,
-                 q=1, growth=2, restart=50, transpose=False, newton_z=None):
+                 q=1, growth=2, restart=50, transpose=False, newton_z=None, smoother="gs", additive=False):
         self.levels = levels
         self.lv = levels[-1]
         self.k = k
@@ -435,8 +435,8 @@ class OseenSetup:
         self.eps_inv = self.prob.eps_inv
         flux = None if winds is None else facet_fluxes(self.lv, winds)
         self.hier = OseenHierarchy(levels, self.prob.nu_c, beta, self.eps_inv, flux,
-                                   transpose=transpose)
-        self.prec = mg.HPMG(self.Aeps, self.lv, k, self.hier, m_p, m_h, q, growth)
+                                   transpose=transpose, smoother=smoother)
+        self.prec = mg.HPMG(self.Aeps, self.lv, k, self.hier, m_p, m_h, q, growth, smoother, additive)
         self.restart = restart
 
     def solve(self, f_qp, lam0=None, rtol=1e-8, atol=1e-10, max_it=500, uzawa_max=50,

@@ -13,7 +13,7 @@ from . import mesh, hdg, mg, krylov
 
 class Setup:
     def __init__(self, coords, cells, n_refine, k, nu, beta, gamma,
-                 m_p=1, m_h=1, q=1, growth=2, harmonic=True):
+                 m_p=1, m_h=1, q=1, growth=2, harmonic=True, smoother="gs", additive=False):
         self.levels = mesh.hierarchy(coords, cells, n_refine)
         self.lv = self.levels[-1]
         self.k = k
@@ -22,8 +22,8 @@ class Setup:
         self.D = self.prob.matrix_D().tocsr()
         self.eps_inv = self.prob.eps_inv
         self.hier = mg.Hierarchy(self.levels, self.prob.nu_c, beta, self.eps_inv,
-                                 harmonic=harmonic)
-        self.prec = mg.HPMG(self.Aeps, self.lv, k, self.hier, m_p, m_h, q, growth)
+                                 harmonic=harmonic, smoother=smoother)
+        self.prec = mg.HPMG(self.Aeps, self.lv, k, self.hier, m_p, m_h, q, growth, smoother, additive)
 
     def inner(self, b, rtol=1e-8, atol=1e-10, max_it=500):
         return krylov.fcg(self.Aeps, b, self.prec, rtol, atol, max_it)

@@ -15,7 +15,8 @@ from . import mesh3d, hdg3d, mg3d, krylov
 
 class Setup3:
     def __init__(self, coords, cells, n_refine, k, nu, beta, gamma,
-                 m_p=2, m_h=2, q=1, growth=2, harmonic=True):
+                 m_p=2, m_h=2, q=1, growth=2, harmonic=True, smoother="gs", additive=False,
+                 patch_relax="edge", patch_smooth="edge"):
         self.levels = mesh3d.hierarchy(coords, cells, n_refine)
         self.lv = self.levels[-1]
         self.k = k
@@ -23,8 +24,10 @@ class Setup3:
         self.Aeps = self.prob.matrix_Aeps().tocsr()
         self.D = self.prob.matrix_D().tocsr()
         self.eps_inv = self.prob.eps_inv
-        self.hier = mg3d.Hierarchy3(self.levels, self.prob.nu_c, beta, self.eps_inv, harmonic=harmonic)
-        self.prec = mg3d.HPMG3(self.Aeps, self.lv, k, self.hier, m_p, m_h, q, growth)
+        self.hier = mg3d.Hierarchy3(self.levels, self.prob.nu_c, beta, self.eps_inv, harmonic=harmonic, smoother=smoother,
+                                    patch=patch_smooth)
+        self.prec = mg3d.HPMG3(self.Aeps, self.lv, k, self.hier, m_p, m_h, q, growth, smoother, additive,
+                                 patch_relax)
 
     def inner(self, b, rtol=1e-8, atol=1e-10, max_it=500):
         return krylov.fcg(self.Aeps, b, self.prec, rtol, atol, max_it)

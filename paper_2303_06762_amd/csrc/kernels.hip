@@ -559,6 +559,24 @@ __global__ void __launch_bounds__(64) k_gs(LevelViewT<TS> L, int p0, double* x, 
   }
 }
 
+template <typename TP>
+__global__ void __launch_bounds__(256) k_patch_correct(const int* __restrict__ pf_ptr, const int* __restrict__ pf,
+                                                       const long* __restrict__ poff, const TP* __restrict__ pinv,
+                                                       int nd, int p0, const double* __restrict__ r, double* x,
+                                                       double damp) {
+  extern __shared__ double res[];
+  const int p = p0 + blockIdx.x;
+  const int f0 = pf_ptr[p], ns = (pf_ptr[p + 1] - f0) * nd;
+  for (int t = threadIdx.x; t < ns; t += blockDim.x) res[t] = r[(long)pf[f0 + t / nd] * nd + t % nd];
+  __syncthreads();
+  const TP* A = pinv + poff[p];
+  for (int t = threadIdx.x; t < ns; t += blockDim.x) {
+    double s = 0.0;
+    for (int j = 0; j < ns; ++j) s += (double)A[(long)j * ns + t] * res[j];
+    x[(long)pf[f0 + t / nd] * nd + t % nd] += damp * s;
+  }
+}
+
 __global__ void k_mode0_extract(int nint, int m, const double* __restrict__ r, double* __restrict__ g0,
                                 double* __restrict__ zero_out) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -993,6 +1011,18 @@ void launch_gs(hipStream_t st, LevelViewT<TS> L, int p0, int p1, double* x, cons
   if (p1 <= p0) return;
   hipLaunchKernelGGL(k_gs<TS>, dim3(p1 - p0), dim3(64), 0, st, L, p0, x, b);
 }
+template <typename TP>
+void launch_patch_correct(hipStream_t st, const int* pf_ptr, const int* pf, const long* poff, const TP* pinv, int nd,
+                          int ns_max, int p0, int p1, const double* r, double* x, double damp) {
+  if (p1 <= p0) return;
+  const int threads = ns_max <= 64 ? 64 : (ns_max <= 128 ? 128 : 256);
+  hipLaunchKernelGGL(k_patch_correct<TP>, dim3(p1 - p0), dim3(threads), (size_t)ns_max * sizeof(double), st, pf_ptr,
+                     pf, poff, pinv, nd, p0, r, x, damp);
+}
+template void launch_patch_correct<double>(hipStream_t, const int*, const int*, const long*, const double*, int, int,
+                                           int, int, const double*, double*, double);
+template void launch_patch_correct<float>(hipStream_t, const int*, const int*, const long*, const float*, int, int,
+                                          int, int, const double*, double*, double);
 template void launch_gs<double>(hipStream_t, LevelViewT<double>, int, int, double*, const double*);
 template void launch_gs<float>(hipStream_t, LevelViewT<float>, int, int, double*, const double*);
 void launch_mode0_extract(hipStream_t st, int nint, int m, const double* r, double* g0, double* zero_out) {

@@ -106,6 +106,15 @@ void launch_apply(hipStream_t st, LevelViewT<TS> L, const double* x, double* y, 
 void launch_gather_cells(hipStream_t st, LevelView L, const double* vK, double* y);
 template <typename TS>
 void launch_gs(hipStream_t st, LevelViewT<TS> L, int p0, int p1, double* x, const double* b);
+// Damped block Jacobi correction (eq. bjac) for the patches [p0, p1) of one
+// colour: x_s += damp * A_ss^-1 r_s from a residual r computed before the
+// sweep, a workgroup per patch.  Patch p holds the nd unknowns of each of
+// its facets pf[pf_ptr[p] ..] (unknown = facet * nd + i), its inverse is
+// column-major at pinv + poff[p]; ns_max bounds the patch sizes (dynamic
+// LDS).  Patches of one colour share no unknown.
+template <typename TP>
+void launch_patch_correct(hipStream_t st, const int* pf_ptr, const int* pf, const long* poff, const TP* pinv, int nd,
+                          int ns_max, int p0, int p1, const double* r, double* x, double damp);
 // out[i] = (float) in[i]
 void launch_to_f32(hipStream_t st, long n, const double* in, float* out);
 // g0 = mode 0 of r (restriction to the lowest-order space); zero_out (if not

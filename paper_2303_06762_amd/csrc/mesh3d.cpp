@@ -237,6 +237,60 @@ void build_edge_patches(Level3& L) {
   }
 }
 
+void build_vertex_patches(Level3& L) {
+  std::vector<std::vector<int>> vf(L.nv), vc(L.nv);
+  for (int f = 0; f < L.nf; ++f) {
+    if (L.int_id[f] < 0) continue;
+    for (int i = 0; i < 3; ++i) vf[L.faces[3 * f + i]].push_back(L.int_id[f]);
+  }
+  for (int c = 0; c < L.nc; ++c)
+    for (int i = 0; i < 4; ++i) vc[L.cells[4 * c + i]].push_back(c);
+  std::vector<int> col(L.nv, -1);
+  int ncol = 0;
+  for (int v = 0; v < L.nv; ++v) {
+    if (vf[v].empty()) continue;
+    std::vector<char> used(64, 0);
+    for (int c : vc[v])
+      for (int j = 0; j < 4; ++j) {
+        const int cc = col[L.cells[4 * c + j]];
+        if (cc >= 0) {
+          if (cc >= (int)used.size()) used.resize(cc + 1, 0);
+          used[cc] = 1;
+        }
+      }
+    int k = 0;
+    while (k < (int)used.size() && used[k]) ++k;
+    col[v] = k;
+    ncol = std::max(ncol, k + 1);
+  }
+  L.ncol = ncol;
+  L.colour_ptr.assign(ncol + 1, 0);
+  L.patch_edge.clear();
+  for (int k = 0; k < ncol; ++k) {
+    L.colour_ptr[k] = (int)L.patch_edge.size();
+    for (int v = 0; v < L.nv; ++v)
+      if (col[v] == k) L.patch_edge.push_back(v);
+  }
+  L.colour_ptr[ncol] = (int)L.patch_edge.size();
+  L.pf_ptr.assign(1, 0);
+  L.pc_ptr.assign(1, 0);
+  L.pf.clear();
+  L.pc.clear();
+  L.max_patch_faces = L.max_patch_cells = 0;
+  for (int v : L.patch_edge) {
+    std::vector<int> fs = vf[v];
+    std::sort(fs.begin(), fs.end());
+    L.pf.insert(L.pf.end(), fs.begin(), fs.end());
+    L.pf_ptr.push_back((int)L.pf.size());
+    std::vector<int> cs = vc[v];
+    std::sort(cs.begin(), cs.end());
+    L.pc.insert(L.pc.end(), cs.begin(), cs.end());
+    L.pc_ptr.push_back((int)L.pc.size());
+    L.max_patch_faces = std::max(L.max_patch_faces, (int)fs.size());
+    L.max_patch_cells = std::max(L.max_patch_cells, (int)cs.size());
+  }
+}
+
 namespace {
 // barycentric coordinates of x in cell T of level C
 void bary(const Level3& C, int T, const double* x, double* lam) {

@@ -26,8 +26,8 @@ struct Level3 {
   std::vector<int> edges;          // [ne][2] sorted pairs, lexicographic order
   std::vector<int> cell_edges;     // [nc][6]
   std::vector<int> cell_dofs;      // [nc][4] interior face id or -1
-  // edge patches with at least one interior face, colour-major (edge order
-  // inside a colour)
+  // edge (or vertex) patches with at least one interior face, colour-major
+  // (edge or vertex order inside a colour)
   int ncol = 0;
   std::vector<int> colour_ptr;     // [ncol + 1]
   std::vector<int> patch_edge;     // [np]
@@ -49,6 +49,12 @@ void refine3(const Level3& C, Level3& F);
 // in edge order take the smallest colour unused by an earlier such edge
 // sharing a cell, so that patches of one colour share no cell.
 void build_edge_patches(Level3& L);
+
+// Vertex patches (Sec. 3.4.2: the interior faces containing a vertex, the
+// cells containing it) in the same fields (patch_edge then holds the
+// vertex), greedily coloured in vertex order so that vertices of one colour
+// lie in no common cell.
+void build_vertex_patches(Level3& L);
 
 // Averaging operator I_{l-1}^l (avgOpt) on the lowest-order unknowns (3 per
 // interior face: n, t1, t2): the coarse CR field at the fine face centroid

@@ -31,7 +31,8 @@ struct DevLev3 {
   double* S = nullptr;
   float* S32 = nullptr;
   int np = 0, ncol = 0, ns_max = 0;
-  std::vector<int> colour_ptr;
+  bool vertex = false;   // vertex patches (Gauss-Seidel by full residual + patch correction per colour)
+  std::vector<int> colour_ptr, hns;
   int *pf_ptr = nullptr, *pf = nullptr, *pc_ptr = nullptr, *pc = nullptr;
   long* poff = nullptr;
   long pinv_len = 0;
@@ -510,9 +511,11 @@ hdgmg_status upload_level(Ctx3* c, const Level3& L, int mF, DevLev3& D) {
   TRY3(upload(c, &D.pc_ptr, L.pc_ptr));
   TRY3(upload(c, &D.pc, L.pc));
   D.hpoff.assign(D.np + 1, 0);
+  D.hns.assign(D.np, 0);
   D.ns_max = 0;
   for (int p = 0; p < D.np; ++p) {
     const long ns = (long)(L.pf_ptr[p + 1] - L.pf_ptr[p]) * 3 * mF;
+    D.hns[p] = (int)ns;
     D.hpoff[p + 1] = D.hpoff[p] + ns * ns;
     D.ns_max = std::max<int>(D.ns_max, (int)ns);
   }
@@ -529,14 +532,24 @@ hdgmg_status upload_level(Ctx3* c, const Level3& L, int mF, DevLev3& D) {
   D.phase_S.assign(D.ncol, 0.0);
   D.phase_P.assign(D.ncol, 0.0);
   D.phase_V.assign(D.ncol, 0.0);
-  for (int col = 0; col < D.ncol; ++col)
+  for (int col = 0; col < D.ncol; ++col) {
+    if (D.vertex) {
+      // vertex patches: a full residual per colour, then the patch inverses
+      D.phase_S[col] = (double)D.nc * D.nK * D.nK;
+      D.phase_V[col] = 2.0 * D.nc * D.nK + 4.0 * D.ndof;
+    }
     for (int p = L.colour_ptr[col]; p < L.colour_ptr[col + 1]; ++p) {
       const double ns = (double)(L.pf_ptr[p + 1] - L.pf_ptr[p]) * 3 * mF;
       const double ncl = L.pc_ptr[p + 1] - L.pc_ptr[p];
-      D.phase_S[col] += ncl * 2.0 * 3 * mF * D.nK;
       D.phase_P[col] += ns * ns;
-      D.phase_V[col] += ncl * D.nK + 3.0 * ns;
+      if (D.vertex) {
+        D.phase_V[col] += 3.0 * ns;
+      } else {
+        D.phase_S[col] += ncl * 2.0 * 3 * mF * D.nK;
+        D.phase_V[col] += ncl * D.nK + 3.0 * ns;
+      }
     }
+  }
   return HDGMG_OK;
 }
 
@@ -618,7 +631,47 @@ double phase_bytes(const Ctx3* c, const DevLev3& D, int col) {
   return D.phase_S[col] * bs + D.phase_P[col] * bp + D.phase_V[col] * 8.0;
 }
 
+// Damped block Jacobi sweep (eq. bjac): r = b - A x once, then every
+// colour's patches add A_ss^-1 r_s / (number of colours)
+void jacobi_sweep(Ctx3* c, DevLev3& D, double* x, const double* b, int cls) {
+  level_apply(c, D, x, D.r, -1.0, b, true);
+  const double damp = 1.0 / D.ncol;
+  for (int col = 0; col < D.ncol; ++col) {
+    const int p0 = D.colour_ptr[col], p1 = D.colour_ptr[col + 1];
+    const int t = kt_begin(c, cls);
+    if (f32(c) && !pinv64(c, D))
+      launch_patch_correct<float>(c->st, D.pf_ptr, D.pf, D.poff, D.pinv32, 3 * D.mF, D.ns_max, p0, p1, D.r, x,
+                                  damp);
+    else
+      launch_patch_correct<double>(c->st, D.pf_ptr, D.pf, D.poff, D.pinv, 3 * D.mF, D.ns_max, p0, p1, D.r, x,
+                                   damp);
+    kt_end(c, cls, t, phase_bytes(c, D, col));
+  }
+}
+
 void sweep(Ctx3* c, DevLev3& D, double* x, const double* b, bool forward, int cls) {
+  if (c->opts.smoother == 1) {
+    jacobi_sweep(c, D, x, b, cls);
+    return;
+  }
+  if (D.vertex) {
+    // vertex patches of one colour share no cell: the residual after the
+    // previous colour, then every patch of the colour corrected at once
+    for (int ci = 0; ci < D.ncol; ++ci) {
+      const int col = forward ? ci : D.ncol - 1 - ci;
+      const int p0 = D.colour_ptr[col], p1 = D.colour_ptr[col + 1];
+      const int t = kt_begin(c, cls);
+      level_apply(c, D, x, D.r, -1.0, b, true);
+      if (f32(c) && !pinv64(c, D))
+        launch_patch_correct<float>(c->st, D.pf_ptr, D.pf, D.poff, D.pinv32, 3 * D.mF, D.ns_max, p0, p1, D.r, x,
+                                    1.0);
+      else
+        launch_patch_correct<double>(c->st, D.pf_ptr, D.pf, D.poff, D.pinv, 3 * D.mF, D.ns_max, p0, p1, D.r, x,
+                                     1.0);
+      kt_end(c, cls, t, phase_bytes(c, D, col));
+    }
+    return;
+  }
   for (int ci = 0; ci < D.ncol; ++ci) {
     const int col = forward ? ci : D.ncol - 1 - ci;
     const int p0 = D.colour_ptr[col], p1 = D.colour_ptr[col + 1];
@@ -675,6 +728,14 @@ void mg_hp(Ctx3* c, const double* r, double* z) {
     launch_fill(c->st, DJ.ndof, 0.0, DJ.u);
     mg_h(c, c->J - 1, c->opts.m_smooth);
     launch_copy(c->st, DJ.ndof, DJ.u, z);
+  } else if (c->opts.additive) {
+    // additive counterpart: relaxation and lowest-order correction of r
+    launch_fill(c->st, KL.ndof, 0.0, z);
+    for (int s = 0; s < c->opts.m_relax; ++s) sweep(c, KL, z, r, true, 0);
+    for (int s = 0; s < c->opts.m_relax; ++s) sweep(c, KL, z, r, false, 0);
+    launch_mode0_extract3(c->st, KL.nint, KL.mF, r, DJ.g, DJ.u);
+    mg_h(c, c->J - 1, c->opts.m_smooth);
+    launch_mode0_add3(c->st, KL.nint, KL.mF, DJ.u, z);
   } else {
     launch_fill(c->st, KL.ndof, 0.0, z);
     for (int s = 0; s < c->opts.m_relax; ++s) sweep(c, KL, z, r, true, 0);
@@ -867,6 +928,12 @@ hdgmg_status d3_setup(const hdgmg_mesh* mesh, int k, double beta, const double* 
     delete c;
     return HDGMG_EINVAL;
   }
+  if (c->opts.smoother < 0 || c->opts.smoother > 1 || c->opts.additive < 0 || c->opts.additive > 1 ||
+      c->opts.patch_relax < 0 || c->opts.patch_relax > 2 || c->opts.patch_smooth < 0 || c->opts.patch_smooth > 2) {
+    err = "invalid smoother, additive or patch options";
+    delete c;
+    return HDGMG_EINVAL;
+  }
   c->k = k;
   c->beta = beta;
   c->eps_inv = gamma;
@@ -900,14 +967,30 @@ hdgmg_status d3_setup(const hdgmg_mesh* mesh, int k, double beta, const double* 
     d3_destroy(c);
     return HDGMG_EMESH;
   }
-  for (auto& L : c->lv) {
-    build_edge_patches(L);
-    if (L.max_patch_faces > 12 || L.max_patch_cells > 12) {
-      err = "mesh: an edge lies in more than 12 faces or cells";
+  // patches: opts.patch_smooth on every level, opts.patch_relax on the
+  // finest for the order-k relaxation (1 vertex, else edge)
+  const bool vrelax = c->opts.patch_relax == 1, vsmooth = c->opts.patch_smooth == 1;
+  auto patches = [&](Level3& L, bool vertex) {
+    if (vertex) {
+      build_vertex_patches(L);
+      if (L.max_patch_faces > 48 || L.max_patch_cells > 32) {
+        err = "mesh: a vertex lies in more than 48 faces or 32 cells";
+        return false;
+      }
+    } else {
+      build_edge_patches(L);
+      if (L.max_patch_faces > 12 || L.max_patch_cells > 12) {
+        err = "mesh: an edge lies in more than 12 faces or cells";
+        return false;
+      }
+    }
+    return true;
+  };
+  for (int l = 0; l < c->J; ++l)
+    if (!patches(c->lv[l], l == c->J - 1 ? vrelax : vsmooth)) {
       d3_destroy(c);
       return HDGMG_EMESH;
     }
-  }
   c->av.resize(c->J);
   for (int l = 1; l < c->J; ++l) build_averaging3(c->lv[l - 1], c->lv[l], c->av[l]);
   *out = c;
@@ -926,15 +1009,23 @@ hdgmg_status d3_setup(const hdgmg_mesh* mesh, int k, double beta, const double* 
     c->err = "table upload failed";
     return fail(HDGMG_EHIP);
   }
-  const Level3& LF = c->lv[c->J - 1];
+  Level3& LF = c->lv[c->J - 1];
+  c->K.vertex = vrelax;
   if ((s = upload_level(c, LF, dims3(k).mF, c->K))) return fail(s);
   {
     std::vector<double> nuv(c->nu_fine);
     if ((s = upload(c, &c->K.nu, nuv))) return fail(s);
   }
+  if (vrelax != vsmooth && !patches(LF, vsmooth)) {
+    d3_destroy(c);
+    *out = nullptr;
+    return HDGMG_EMESH;
+  }
   c->cr.resize(c->J);
-  for (int l = 0; l < c->J; ++l)
+  for (int l = 0; l < c->J; ++l) {
+    c->cr[l].vertex = vsmooth;
     if ((s = upload_level(c, c->lv[l], 1, c->cr[l]))) return fail(s);
+  }
   // per-level viscosities: the finest as given, coarser the mean of the eight children
   {
     std::vector<std::vector<double>> nus(c->J);
@@ -1073,17 +1164,17 @@ hdgmg_status d3_assemble(Ctx3* c) {
   // symmetric form (cell blocks nK(nK+1)/2 words, patch inverses
   // ns(ns+1)/2, the coarsest inverse n0(n0+1)/2), plus the vectors
   auto tri = [](double n) { return n * (n + 1.0) / 2.0; };
-  auto sweep_c = [&](const Level3& L, const DevLev3& D) {
+  auto sweep_c = [&](const DevLev3& D) {
     double pb = 0.0;
-    for (int q = 0; q < D.np; ++q) pb += tri(3.0 * D.mF * (L.pf_ptr[q + 1] - L.pf_ptr[q]));
+    for (int q = 0; q < D.np; ++q) pb += tri((double)D.hns[q]);
     return D.nc * tri(D.nK) * b + pb * (pinv64(c, D) ? 8.0 : b) + 3.0 * 8.0 * D.ndof;
   };
   auto res_c = [&](const DevLev3& D) { return D.nc * tri(D.nK) * b + 3.0 * 8.0 * D.ndof; };
   double vc = 0.0;
-  if (c->k > 0) vc += 2.0 * c->opts.m_relax * sweep_c(c->lv[c->J - 1], c->K) + res_c(c->K);
+  if (c->k > 0) vc += 2.0 * c->opts.m_relax * sweep_c(c->K) + res_c(c->K);
   double vis = 1.0, ml = c->opts.m_smooth;
   for (int l = c->J - 1; l >= 1; --l) {
-    vc += vis * (2.0 * ml * sweep_c(c->lv[l], c->cr[l]) + res_c(c->cr[l]));
+    vc += vis * (2.0 * ml * sweep_c(c->cr[l]) + res_c(c->cr[l]));
     vis *= c->opts.cycle;
     ml *= c->opts.vcycle_growth;
   }

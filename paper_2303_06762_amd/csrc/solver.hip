@@ -459,7 +459,7 @@ hdgmg_status upload_level(hdgmg_ctx* ctx, const Level& L, int m, DevLevel& D) {
   D.colour_ptr = L.colour_ptr;
   // streaming kernels pay off on large levels; small ones keep the one-launch
   // Gauss-Seidel phase
-  D.fast = L.max_patch_facets <= FAST_NF && (long)L.nint * 2 * m >= ctx->opts.stream_dofs;
+  D.fast = L.max_patch_facets <= FAST_NF && (long)L.nint * 2 * m >= ctx->opts.stream_dofs && ctx->opts.smoother == 0;
   D.full = ctx->opts.oseen != 0;
   D.sp_words = fast_cell_words(D.nK, D.full);
   if (D.fast) {
@@ -617,7 +617,32 @@ double phase_bytes(const hdgmg_ctx* ctx, const DevLevel& D, int level, int c) {
 // One Gauss-Seidel sweep over the colours.  x_zero: x is zero on entry, so
 // the first colour phase of the streaming layout needs no cell apply (its
 // residual is b).
+void level_apply(hdgmg_ctx* ctx, DevLevel& D, const double* x, double* y, double alpha, const double* b,
+                 int cls, bool vc);
+
+// Damped block Jacobi sweep (eq. bjac): r = b - A x once, then every
+// colour's patches add damp A_ss^-1 r_s (launch-per-colour layout only).
+void jacobi_sweep(hdgmg_ctx* ctx, DevLevel& D, double* x, const double* b, int level) {
+  const int nc = (int)D.colour_ptr.size() - 1;
+  const int cls = level < 0 ? 0 : 2;
+  level_apply(ctx, D, x, D.r, -1.0, b, cls, true);
+  for (int c = 0; c < nc; ++c) {
+    int t = kt_begin(ctx, cls);
+    if (D.f32)
+      launch_patch_correct<float>(ctx->st, D.pf_ptr, D.pf, D.pinv_off, D.pinv32, 2 * D.m, D.max_ns,
+                                  D.colour_ptr[c], D.colour_ptr[c + 1], D.r, x, 1.0 / nc);
+    else
+      launch_patch_correct<double>(ctx->st, D.pf_ptr, D.pf, D.pinv_off, D.pinv, 2 * D.m, D.max_ns,
+                                   D.colour_ptr[c], D.colour_ptr[c + 1], D.r, x, 1.0 / nc);
+    kt_end(ctx, cls, t, phase_bytes(ctx, D, level, c));
+  }
+}
+
 void sweep(hdgmg_ctx* ctx, DevLevel& D, double* x, const double* b, bool forward, int level, bool x_zero = false) {
+  if (ctx->opts.smoother == 1) {
+    jacobi_sweep(ctx, D, x, b, level);
+    return;
+  }
   const int nc = (int)D.colour_ptr.size() - 1;
   for (int i = 0; i < nc; ++i) {
     int c = forward ? i : nc - 1 - i;
@@ -810,6 +835,15 @@ void mg_hp_body(hdgmg_ctx* ctx, const double* r, double* z) {
     return;
   }
   launch_fill(ctx->st, KL.ndof, 0.0, z);
+  if (ctx->opts.additive) {
+    // additive counterpart: relaxation and lowest-order correction of r
+    for (int s = 0; s < ctx->opts.m_relax; ++s) sweep(ctx, KL, z, r, true, -1, s == 0);
+    for (int s = 0; s < ctx->opts.m_relax; ++s) sweep(ctx, KL, z, r, false, -1);
+    launch_mode0_extract(ctx->st, KL.nint, KL.m, r, DJ.g, DJ.u);
+    mg_h(ctx, ctx->J - 1, ctx->opts.m_smooth, true);
+    launch_mode0_add(ctx->st, KL.nint, KL.m, DJ.u, z);
+    return;
+  }
   for (int s = 0; s < ctx->opts.m_relax; ++s) sweep(ctx, KL, z, r, true, -1, s == 0);
   apply_k(ctx, z, KL.r, -1.0, r, true);
   launch_mode0_extract(ctx->st, KL.nint, KL.m, KL.r, DJ.g, DJ.u);  // and DJ.u = 0
@@ -1261,7 +1295,7 @@ hdgmg_status upload_vals(hdgmg_ctx* ctx, const std::vector<double>& h, const voi
 // row of the patch inverse (host FP64 factorisation), structure-of-arrays.
 hdgmg_status build_coarse(hdgmg_ctx* ctx) {
   ctx->Lc = -1;
-  if (ctx->opts.coarse_dofs <= 0) return HDGMG_OK;
+  if (ctx->opts.coarse_dofs <= 0 || ctx->opts.smoother != 0) return HDGMG_OK;
   int Lc = -1, vec = 0, nsmax = 0;
   for (int l = 0; l < ctx->J && l < COARSE_MAX_LEVELS; ++l) {
     const Level& L = ctx->lv[l];
@@ -1420,7 +1454,9 @@ hdgmg_status build_record_levels(hdgmg_ctx* ctx) {
     // records replace the streaming pair (cell apply + patch relaxation) on
     // the launched lowest-order levels (32-bit fields beyond 16-bit facet
     // indices); stream_dofs = 0 keeps the streaming kernels on every level
-    if (L.nint > REC_MAX_FACETS || 2 * L.max_patch_facets > 32 || (D.fast && ctx->opts.stream_dofs == 0)) continue;
+    if (L.nint > REC_MAX_FACETS || 2 * L.max_patch_facets > 32 || (D.fast && ctx->opts.stream_dofs == 0) ||
+        ctx->opts.smoother != 0)
+      continue;
     const bool wide = ctx->opts.rec_wide || L.nint > 65535 || 2 * L.nint > (int)REC_DOF_MASK;
     LevelRecords R;
     TRY(level_records(ctx, l, GS_REC_THREADS, R, true, wide));
@@ -1692,6 +1728,10 @@ void hdgmg_default_opts(hdgmg_opts* o) {
   o->transpose = 0;
   o->coarse_dense = 1;
   o->rec_wide = 0;
+  o->smoother = 0;
+  o->additive = 0;
+  o->patch_relax = 0;
+  o->patch_smooth = 0;
 }
 
 const char* hdgmg_last_error(const hdgmg_ctx* ctx) {
@@ -1782,8 +1822,10 @@ hdgmg_status hdgmg_setup(const hdgmg_mesh* mesh, int k, double beta, const doubl
       ctx->opts.vcycle_precision < 0 || ctx->opts.vcycle_precision > 2 || ctx->opts.oseen < 0 ||
       ctx->opts.oseen > 1 || ctx->opts.restart < 1 || ctx->opts.restart > 64 || ctx->opts.transpose < 0 ||
       ctx->opts.transpose > 1 || (ctx->opts.transpose && !ctx->opts.oseen) || ctx->opts.coarse_dense < 0 ||
-      ctx->opts.coarse_dense > 1 || ctx->opts.rec_wide < 0 || ctx->opts.rec_wide > 1) {
-    g_setup_error = "invalid options";
+      ctx->opts.coarse_dense > 1 || ctx->opts.rec_wide < 0 || ctx->opts.rec_wide > 1 || ctx->opts.smoother < 0 ||
+      ctx->opts.smoother > 1 || ctx->opts.additive < 0 || ctx->opts.additive > 1 || ctx->opts.patch_relax < 0 ||
+      ctx->opts.patch_relax > 1 || ctx->opts.patch_smooth < 0 || ctx->opts.patch_smooth > 1) {
+    g_setup_error = "invalid options (triangles: vertex patches only)";
     delete ctx;
     return HDGMG_EINVAL;
   }

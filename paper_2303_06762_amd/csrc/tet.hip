@@ -734,20 +734,24 @@ __global__ void k_face_gather3(int nint, int m3, int nK, const int* __restrict__
 
 constexpr int PMAX_CELLS = 12;  // cells around an edge handled per patch
 constexpr int PMAX_FACES = 12;
+// limits of the patch-inverse kernel (vertex patches of tetrahedral meshes:
+// 24 cells and 36 interior faces around an interior vertex of a Kuhn mesh)
+constexpr int PINV_MAX_CELLS = 32;
+constexpr int PINV_MAX_FACES = 48;
 
 __global__ void __launch_bounds__(NT) k_patch_inverse3(Level3View<double> L, const int* __restrict__ pf_ptr,
                                                        const int* __restrict__ pf, const int* __restrict__ pc_ptr,
                                                        const int* __restrict__ pc, const long* __restrict__ poff,
                                                        int p0, int ns_max, double* ws, double* pinv,
                                                        int* status) {
-  __shared__ int slot[PMAX_CELLS][4];
+  __shared__ int slot[PINV_MAX_CELLS][4];
   __shared__ double pv;
-  __shared__ double fct[PMAX_FACES * 3 * MF3MAX];
+  __shared__ double fct[PINV_MAX_FACES * 3 * MF3MAX];
   const int p = p0 + blockIdx.x, tid = threadIdx.x;
   const int f0 = pf_ptr[p], nf = pf_ptr[p + 1] - f0, c0 = pc_ptr[p], ncl = pc_ptr[p + 1] - c0;
   const int m3 = 3 * L.mF, ns = nf * m3, nK = L.nK, w = 2 * ns;
   double* A = ws + (long)blockIdx.x * ns_max * 2 * ns_max;
-  if (nf > PMAX_FACES || ncl > PMAX_CELLS) {
+  if (nf > PINV_MAX_FACES || ncl > PINV_MAX_CELLS) {
     if (tid == 0) atomicOr(status, 4);
     return;
   }

@@ -56,6 +56,8 @@ CASES = {
     "k1_per_level": (2, 2, 1, 0.1, 1.0, 20.0, True, dict(coarse_dofs=0)),
     "k2_split": (2, 3, 2, 0.1, 1.0, 20.0, True, dict(coarse_dofs=200)),
     "k2_restart5": (2, 2, 2, 0.1, 1.0, 20.0, True, dict(restart=5)),
+    "k2_jacobi": (2, 2, 2, 0.1, 1.0, 20.0, True, dict(smoother=1)),
+    "k1_additive": (2, 2, 1, 0.1, 1.0, 20.0, True, dict(additive=1)),
 }
 
 _ORACLE = {}
@@ -78,7 +80,8 @@ def oracle_case(name):
     wq = np.array([winds[K](pr0.elems[K].xq) for K in range(lv.n_cells)])
     dirichlet = oseen.lid_dirichlet(lv, k) if lid else None
     restart = kw.get("restart", 50)
-    S = oseen.OseenSetup(levels, k, nu, beta, 1e2, winds, dirichlet, restart=restart)
+    S = oseen.OseenSetup(levels, k, nu, beta, 1e2, winds, dirichlet, restart=restart,
+                         smoother="jacobi" if kw.get("smoother") else "gs", additive=bool(kw.get("additive")))
     f = synth.source_uniform(7, 1, lv.n_cells, nq)[0]
     _ORACLE[name] = (c, t, levels, S, wq, f, dirichlet)
     return _ORACLE[name]

@@ -73,6 +73,22 @@ def test_edge_colouring_is_proper():
     assert covered == set(np.where(lv.interior)[0].tolist())
 
 
+def test_vertex_colouring_is_proper_and_patches_are_the_vertex_stars():
+    lv = mesh3d.Level3(*synth.kuhn_cube(3))
+    pats = lv.vertex_patches()
+    col = lv.vertex_colours(pats)
+    for K in range(lv.n_cells):
+        cs = [col[v] for v in lv.cells[K] if col[v] >= 0]
+        assert len(cs) == len(set(cs))
+    # an interior vertex of a Kuhn mesh lies in 24 cells and 36 faces, all interior
+    inner = np.where(np.all((lv.coords > 0) & (lv.coords < 1), axis=1))[0]
+    for v in inner:
+        assert len(pats[v]) == 36
+    # boundary vertices with interior faces (three vertices each) keep theirs
+    covered = {f for p in pats for f in p}
+    assert covered == set(np.where(lv.interior)[0].tolist())
+
+
 # ---------------------------------------------------------- quadrature ----
 @pytest.mark.parametrize("n", [2, 3, 5])
 def test_tet_rule_exact_to_degree_2n_minus_1(n):
