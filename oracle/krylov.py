@@ -14,8 +14,14 @@
 import numpy as np
 
 
+class Breakdown(ArithmeticError):
+    """Flexible CG cannot continue: z.r <= 0 or p.Ap <= 0 (the preconditioner
+    or the operator is not positive definite on the Krylov space; the "NA"
+    entries of the paper's tables)."""
+
+
 def fcg(A, b, prec, rtol=1e-8, atol=1e-10, max_it=500, x0=None):
-    """Returns (x, iterations, residual history)."""
+    """Returns (x, iterations, residual history); raises Breakdown."""
     x = np.zeros_like(b) if x0 is None else x0.copy()
     r = b - A @ x
     hist = [np.linalg.norm(r)]
@@ -28,7 +34,10 @@ def fcg(A, b, prec, rtol=1e-8, atol=1e-10, max_it=500, x0=None):
     it = 0
     while it < max_it:
         q = A @ p
-        alpha = zr / (p @ q)
+        pq = p @ q
+        if not (zr > 0.0 and pq > 0.0):
+            raise Breakdown(f"z.r = {zr:.3e}, p.Ap = {pq:.3e} at iteration {it + 1}")
+        alpha = zr / pq
         x += alpha * p
         r_new = r - alpha * q
         it += 1

@@ -903,13 +903,14 @@ hdgmg_status fcg(hdgmg_ctx* ctx, const KrylovScratch& W, const double* b, double
     HIPC(hipMemcpyAsync(hs, W.sc, sizeof(hs), hipMemcpyDeviceToHost, st));
     HIPC(hipStreamSynchronize(st));
     ++it;
-    if (!std::isfinite(hs[SC_RR]) || !std::isfinite(hs[SC_PQ]) || !std::isfinite(hs[SC_ZR])) {
-      ctx->err = "non-finite value in flexible CG";
-      return HDGMG_ENONFINITE;
-    }
+    // breakdown first: with z.r = 0 or p.Ap = 0 the step itself is 0/0
     if (hs[SC_PQ] <= 0.0 || hs[SC_ZR] <= 0.0) {
       ctx->err = "flexible CG breakdown (p.Ap <= 0 or z.r <= 0)";
       return HDGMG_EBREAKDOWN;
+    }
+    if (!std::isfinite(hs[SC_RR]) || !std::isfinite(hs[SC_PQ]) || !std::isfinite(hs[SC_ZR])) {
+      ctx->err = "non-finite value in flexible CG";
+      return HDGMG_ENONFINITE;
     }
     rn = std::sqrt(hs[SC_RR]);
     if (its_out) *its_out = it;

@@ -41,6 +41,14 @@ def source(X, nu, beta):
     return -nu * np.stack([lap_ux, lap_uy], axis=-1) + beta * u + gp
 
 
+def ns_source(X, nu):
+    """Stationary Navier-Stokes (Sec. 5.1.2): -nu Lap u + (u . grad) u +
+    grad p for the same u and p."""
+    u = velocity(X)
+    conv = np.einsum("...ij,...j->...i", grad_velocity(X), u)
+    return source(X, nu, 0.0) + conv
+
+
 # Cavity-type solution with a tangential boundary velocity on the top side:
 # u = curl(psi), psi = g(x) h(y), h(y) = y^2 (1 - y), so u.n = 0 on the whole
 # boundary, u = 0 on the left, right and bottom sides and u_x = -g(x) on top.

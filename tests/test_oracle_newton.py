@@ -103,3 +103,27 @@ def test_method_solves_the_newton_systems():
     assert np.abs(r["lam"] - lam_d).max() <= 1e-7 * np.abs(lam_d).max()
     assert np.abs(r["lam"] - ref[i]["lam"]).max() <= 1e-7 * np.abs(lam_d).max()
     assert max(r["its"]) <= 60, r["its"]
+
+
+def test_navier_stokes_convergence_order():
+    # Sec. 5.1.2: Alg. 3 (direct linear solves) on the manufactured solution
+    # with the convection (u . grad) u in the source converges at order k+1
+    # in the velocity, as for the generalized Stokes problem
+    from tests import manufactured as mf
+    k, nu = 1, 0.05
+    errs = []
+    for n in (4, 8):
+        c, t = synth.kuhn_square(n)
+        levels = mesh.hierarchy(c, t, 0)
+        lv = levels[-1]
+        pr = hdg.Problem(lv, k, nu, 0.0, 1.0)
+        X = np.array([e.xq for e in pr.elems])
+        f = mf.ns_source(X, nu)
+        steps = oseen.picard_newton(levels, k, nu, 0.0, 1e2, f, None, eps_picard=1e-3, direct=True,
+                                    newton_rtol=1e-12, newton_atol=1e-14, max_newton=6)
+        assert steps[-1]["kind"] == "newton"
+        u = steps[-1]["u"]
+        w = np.array([e.wq for e in pr.elems])
+        errs.append(np.sqrt(np.sum(w[..., None] * (u - mf.velocity(X)) ** 2)))
+    rate = np.log2(errs[0] / errs[1])
+    assert rate > k + 1 - 0.3, errs
