@@ -159,36 +159,40 @@ def oseen_workload(hd, synth, torch, np, steps, re, k=3, n_refine=5):
     return out
 
 
-def alg3_workload(hd, synth, torch, np, re, k=3, n_refine=5):
-    """Alg. 3 on the lid-driven cavity of oseen_workload (128x128, k = 3,
-    beta = 0, nu = 1/Re, same body force) in the paper's solver setting:
-    (nu eps)^-1 = 1e6 and two AL-Uzawa steps per linear solve.  A Stokes
-    solve, Picard steps until ||u_n - u_{n-1}||_0 < 1e-4, then Newton steps
-    until ||u_n - u_{n-1}||_0 <= max(1e-8 ||u_n||_0, 1e-10), every inner
-    solve by FGMRES(50) with the FP32-storage V-cycle to rel. res. 1e-8.
-    Reports the average FGMRES iterations per inner solve in each phase (the
-    quantity the paper tabulates) and the wall time of the whole iteration
+def lid_solver(hd, synth, torch, k, n_refine, beta, nu, **kw):
+    """A context on the paper's cavity: the unit square from 2x2 Kuhn
+    squares (level n_refine + 1), lid u = (4x(1-x), 0) on y = 1 (its facet
+    L^2 projection), no-slip elsewhere, (nu eps)^-1 = 1e6, two AL-Uzawa
+    steps per linear solve (Sec. 5 settings)."""
+    c, t = synth.kuhn_square(2)
+    s = hd.Solver(c, t, n_refine, k, beta, nu, 1e6 * nu, uzawa_max=2, uzawa_tol=-1.0, **kw)
+    ends = s.boundary_facets().cpu().numpy()
+    lid = synth.lid_coefficients(ends, k, lambda x: 4.0 * x * (1.0 - x))
+    s.set_dirichlet(torch.as_tensor(lid, device="cuda"))
+    return s
+
+
+def alg3_workload(hd, synth, torch, np, re, k=3, n_refine=6):
+    """Alg. 3 on the paper's lid-driven cavity (Sec. 5.2.2): level 7
+    (128x128), k = 3, beta = 0, nu = 1/Re, f = 0, (nu eps)^-1 = 1e6, two
+    AL-Uzawa steps per linear solve, m_p = m_h = 1.  A Stokes solve, Picard
+    steps until ||u_n - u_{n-1}||_0 < 1e-4, then Newton steps until
+    ||u_n - u_{n-1}||_0 <= max(1e-8 ||u_n||_0, 1e-10), every inner solve by
+    FGMRES(50) with the FP64 V-cycle to rel. res. 1e-8.  Reports the
+    average FGMRES iterations per inner solve in each phase (the quantity
+    the paper tabulates) and the wall time of the whole iteration
     (re-assemblies included)."""
-    c, t = synth.kuhn_square(4)
     nu = 1.0 / re
-    s = hd.Solver(c, t, n_refine, k, 0.0, nu, 1e6 * nu, oseen=1, vcycle_precision=1, uzawa_max=2,
-                  uzawa_tol=-1.0)
-    X = s.data_points().cpu().numpy()
-    coef = synth.uniform_pm1(2, 0, (2, 3, 3))
-    f = np.zeros(X.shape)
-    for i in range(2):
-        for a in range(3):
-            for b in range(3):
-                f[..., i] += coef[i, a, b] * np.sin((a + 1) * np.pi * X[..., 0]) * np.sin((b + 1) * np.pi * X[..., 1])
-    f = torch.as_tensor(f, device="cuda")
+    s = lid_solver(hd, synth, torch, k, n_refine, 0.0, nu, oseen=1)
+    f = torch.zeros((s.n_cells, s.n_q, 2), dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    s.set_dirichlet_velocity(torch.as_tensor(synth.lid_velocity(s.boundary_facets().cpu().numpy()), device="cuda"))
     out = hd.picard_newton(s, f, eps_picard=1e-4, newton_rtol=1e-8, newton_atol=1e-10)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    res = {"workload": f"lid-driven cavity, 128x128 ({s.n_cells} cells), k={k}, Re={re:g}, beta=0, "
-                       f"(nu eps)^-1=1e6, two Uzawa steps; Alg. 3: Picard to 1e-4, then Newton to 1e-8",
+    res = {"workload": f"lid-driven cavity (lid 4x(1-x), f = 0), level {n_refine + 1} ({s.n_cells} cells), "
+                       f"k={k}, Re={re:g}, beta=0, (nu eps)^-1=1e6, two Uzawa steps, m=1; Alg. 3: Picard "
+                       f"to 1e-4, then Newton to 1e-8",
            "n_skel": s.n_skel, "wall_s": wall, "steps": [o["kind"] for o in out],
            "du": [o["du"] for o in out], "status": [o["status"] for o in out]}
     for kind in ("picard", "newton"):
@@ -197,6 +201,48 @@ def alg3_workload(hd, synth, torch, np, re, k=3, n_refine=5):
         res[f"solve_s_{kind}"] = float(sum(o["info"]["t_solve"] for o in out if o["kind"] == kind))
     s.close()
     return res
+
+
+def paper_tables(hd, synth, torch, np):
+    """The paper's cavity runs beside its tables: PCG counts of the Stokes
+    cavity (Sec. 5.2.1; k = 0..3, levels 4-7, beta in {0, 1e3}, m in {1, 2},
+    variable V- and W-cycle) and average PGM counts of Alg. 3 on the
+    Navier-Stokes cavity (Sec. 5.2.2; k = 2, 3, levels 5-8, nu in {1, 1e-2,
+    1e-3}, m = 1).  One JSON line per case."""
+    for k in range(4):
+        for level in range(4, 8):
+            for cyc in (1, 2):
+                for beta in (0.0, 1e3):
+                    for m in (1, 2):
+                        kw = dict(cycle=cyc, m_relax=m, m_smooth=m)
+                        if cyc == 2:
+                            kw["vcycle_growth"] = 1
+                        s = lid_solver(hd, synth, torch, k, level - 1, beta, 1.0, **kw)
+                        s.assemble()
+                        f = torch.zeros((s.n_cells, s.n_q, 2), dtype=torch.float64, device="cuda")
+                        try:
+                            u, p, state, info, st = s.solve(f)
+                            its, status = info["its"], st
+                        except hd.HdgmgError as e:
+                            its, status = None, e.status
+                        print(json.dumps({"table": "stokesLid", "d": 2, "k": k, "level": level,
+                                          "cycle": "V" if cyc == 1 else "W", "beta": beta, "m": m,
+                                          "pcg_its": its, "status": status}), flush=True)
+                        s.close()
+    for k in (2, 3):
+        for level in range(5, 9):
+            for nu in (1.0, 1e-2, 1e-3):
+                s = lid_solver(hd, synth, torch, k, level - 1, 0.0, nu, oseen=1)
+                f = torch.zeros((s.n_cells, s.n_q, 2), dtype=torch.float64, device="cuda")
+                t0 = time.perf_counter()
+                out = hd.picard_newton(s, f, eps_picard=1e-4, newton_rtol=1e-8, newton_atol=1e-10)
+                rec = {"table": "nsLid2D", "k": k, "level": level, "nu": nu, "wall_s": time.perf_counter() - t0,
+                       "steps": [o["kind"] for o in out], "status": max(o["status"] for o in out)}
+                for kind in ("picard", "newton"):
+                    its = [i for o in out if o["kind"] == kind for i in o["info"]["its"]]
+                    rec[f"avg_pgm_its_{kind}"] = float(np.mean(its)) if its else None
+                print(json.dumps(rec), flush=True)
+                s.close()
 
 
 def adjoint_workload(hd, synth, torch, np, nrhs):
@@ -497,6 +543,7 @@ def main():
     ap.add_argument("--no-oseen", action="store_true", help="skip the lid-driven cavity Picard workload")
     ap.add_argument("--picard-steps", type=int, default=10)
     ap.add_argument("--re", type=float, default=100.0)
+    ap.add_argument("--alg3-re", type=float, default=1000.0, help="Reynolds number of the Alg. 3 cavity")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the batch-gradient workload")
     ap.add_argument("--adjoint-rhs", type=int, default=16)
     ap.add_argument("--n-refine", type=int, default=6)
@@ -504,6 +551,8 @@ def main():
                     help="parameter sweeps instead of the bench line: the 256x256 generalized Stokes "
                          "workload over k, beta, gamma and V-cycle precision, and the cavity over Re; "
                          "one JSON line per case, then a summary line")
+    ap.add_argument("--tables", action="store_true",
+                    help="the paper's Stokes and Navier-Stokes cavity runs (one JSON line per case)")
     ap.add_argument("--profile-solves", type=int, default=2)
     ap.add_argument("--profile-run", action="store_true",
                     help="counter-collection run: a 1 GiB device copy (calibration of the HBM "
@@ -516,7 +565,7 @@ def main():
         sys.exit(2)
     import numpy as np
     cpu = None
-    if not (a.no_cpu_baseline or a.sweep or a.profile_run):
+    if not (a.no_cpu_baseline or a.sweep or a.profile_run or a.tables):
         # before anything touches the GPU: the workers are forked
         workers = a.cpu_workers or min(16, os.cpu_count() or 1)
         progress(f"CPU oracle baseline on {workers} processes")
@@ -529,6 +578,9 @@ def main():
     c, t = synth.kuhn_square(4)
     if a.sweep:
         sweep(hd, synth, torch, np, c, t, a)
+        return
+    if a.tables:
+        paper_tables(hd, synth, torch, np)
         return
     if a.profile_run:
         # calibration: an elementwise kernel reading exactly 1 GiB and
@@ -619,7 +671,7 @@ def main():
         if not a.no_oseen:
             out["oseen"] = oseen_workload(hd, synth, torch, np, a.picard_steps, a.re)
             progress("cavity Picard done")
-            out["alg3"] = alg3_workload(hd, synth, torch, np, a.re)
+            out["alg3"] = alg3_workload(hd, synth, torch, np, a.alg3_re)
             progress("Alg. 3 done")
         if not a.no_adjoint:
             out["adjoint"] = adjoint_workload(hd, synth, torch, np, a.adjoint_rhs)

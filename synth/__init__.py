@@ -110,6 +110,28 @@ def lid_velocity(ends, top=1.0):
     return g
 
 
+def lid_coefficients(ends, k, profile, top=1.0):
+    """Tangential boundary coefficients [n_boundary_facets][k+1] of the lid
+    velocity (profile(x), 0) on the facets of the side y = top (zero
+    elsewhere): the facet L^2 projection onto the modes
+    phi_j(s) = sqrt(2j+1) P_j(2s-1), s running from the facet's first end
+    point to its second (the tangent's direction); ends: [nb][2][2].  The
+    lid of the paper's cavity is profile(x) = 4x(1-x)."""
+    ends = np.asarray(ends, dtype=np.float64)
+    out = np.zeros((ends.shape[0], k + 1))
+    xg, wg = np.polynomial.legendre.leggauss(k + 4)
+    s, w = 0.5 * (xg + 1.0), 0.5 * wg
+    phi = np.stack([np.sqrt(2 * j + 1) * np.polynomial.legendre.legval(2 * s - 1, np.eye(k + 1)[j])
+                    for j in range(k + 1)])
+    for i, (a, b) in enumerate(ends):
+        if abs(a[1] - top) >= 1e-12 or abs(b[1] - top) >= 1e-12:
+            continue
+        tx = (b[0] - a[0]) / np.hypot(*(b - a))
+        x = a[0] + s * (b[0] - a[0])
+        out[i] = phi @ (w * profile(x) * tx)
+    return out
+
+
 def source_uniform(seed, nrhs, n_cells, n_qp, dim=2, stream=0):
     """f at the data quadrature points, i.i.d. uniform[-1,1):
     array [nrhs][n_cells][n_qp][dim]."""

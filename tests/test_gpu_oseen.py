@@ -185,6 +185,11 @@ def test_picard_matches_oracle():
     bd = host(lid(s))
     ref_bd = np.array([lid_o[E] for E in np.where(lv.int_id < 0)[0]])
     assert np.abs(bd - ref_bd).max() <= 1e-14
+    # the input generator's facet projection of a lid profile uses the
+    # library's facet basis and orientation (a constant profile gives the
+    # same coefficients)
+    prof = synth.lid_coefficients(host(s.boundary_facets()), k, lambda x: np.ones_like(x))
+    assert np.abs(prof - bd).max() <= 1e-14
     out = hd.picard(s, dev(f), 3, None)
     for (u, p, state, info, st), r in zip(out, ref):
         assert st == 0
