@@ -394,7 +394,8 @@ hdgmg_status hdgmg_set_newton(hdgmg_ctx* ctx, const double* state_prev);
  *          (the outputs then hold that step's solution; the stream is
  *          synchronised)
  * Requires opts.oseen = 1, opts.transpose = 0 (ESTATE), Newton k >= 1.
- * Allocates two buffers (previous velocity and state) at the first call.
+ * Allocates two buffers (previous velocity and state) at the first call,
+ * a third (the pseudo-time load) at the first call with dt_inv > 0.
  * Returns the largest status of the steps (NOT_CONVERGED if any inner
  * solve did not converge), or the first negative one. */
 #define HDGMG_MAX_ALG3 128
@@ -404,6 +405,13 @@ typedef struct {
   double newton_atol;      /* absolute Newton stop (1e-10)                  */
   int max_picard;          /* Picard step cap                                */
   int max_newton;          /* Newton step cap (0: Picard only)               */
+  double dt_inv;           /* 0: none; > 0: the Stokes and Picard steps are
+                              backward-Euler pseudo-time steps of size
+                              1/dt_inv (Sec. 5.2.2): dt_inv u added to the
+                              operator (beta + dt_inv) and dt_inv u_{n-1} to
+                              the load (u_{-1} = 0); at their fixed point the
+                              two cancel; the Newton steps solve the steady
+                              system                                       */
 } hdgmg_alg3_opts;
 typedef struct {
   int n_steps;

@@ -509,13 +509,18 @@ def l2_diff(prob, u1, u2):
 
 
 def picard_newton(levels, k, nu, beta, gamma, f_qp, dirichlet=None, eps_picard=1e-4, newton_rtol=1e-8,
-                  newton_atol=1e-10, max_picard=50, max_newton=20, direct=False, solve_kw=None, **kw):
+                  newton_atol=1e-10, max_picard=50, max_newton=20, direct=False, solve_kw=None, dt_inv=0.0,
+                  **kw):
     """Alg. 3: a Stokes solve, Picard steps until ||u_n - u_{n-1}||_0 <
     eps_picard, then Newton steps until ||u_n - u_{n-1}||_0 <=
     max(newton_rtol ||u_n||_0, newton_atol); every step starts from the
     previous skeleton vector, a Newton step's AL-Uzawa loop from the
-    previous pressure.  solve_kw: options of OseenSetup.solve.  Returns the
-    per-step dicts (kind, lam, p0, u, its, du)."""
+    previous pressure.  dt_inv > 0: the Stokes and Picard steps are
+    backward-Euler pseudo-time steps (Sec. 5.2.2), (u_n - u_{n-1}) dt_inv
+    added to the equation: beta + dt_inv in the operator, f + dt_inv
+    u_{n-1} as the load (u_{-1} = 0).  solve_kw: options of
+    OseenSetup.solve.  Returns the per-step dicts (kind, lam, p0, u, its,
+    du)."""
     out = []
     solve_kw = solve_kw or {}
     winds = zs = lam = u_prev = p_prev = None
@@ -523,16 +528,19 @@ def picard_newton(levels, k, nu, beta, gamma, f_qp, dirichlet=None, eps_picard=1
     n_p = n_n = 0
     while True:
         nz_ = zs if kind == "newton" else None
+        pt = dt_inv > 0.0 and kind != "newton"
+        beta_s = beta + dt_inv if pt else beta
+        f_s = f_qp + dt_inv * u_prev if pt and u_prev is not None else f_qp
         if direct:
-            prob = OseenProblem(levels[-1], k, nu, beta, gamma, winds, dirichlet, newton_z=nz_)
-            lam_d, p_d = prob.solve_direct(f_qp)
+            prob = OseenProblem(levels[-1], k, nu, beta_s, gamma, winds, dirichlet, newton_z=nz_)
+            lam_d, p_d = prob.solve_direct(f_s)
             r = dict(lam=lam_d, p0=p_d, its=[])
             S = None
         else:
-            S = OseenSetup(levels, k, nu, beta, gamma, winds, dirichlet, newton_z=nz_, **kw)
+            S = OseenSetup(levels, k, nu, beta_s, gamma, winds, dirichlet, newton_z=nz_, **kw)
             prob = S.prob
-            r = S.solve(f_qp, lam0=lam, p_init=p_prev if kind == "newton" else None, **solve_kw)
-        u, _, _, _ = prob.recover(r["lam"], r["p0"], f_qp)
+            r = S.solve(f_s, lam0=lam, p_init=p_prev if kind == "newton" else None, **solve_kw)
+        u, _, _, _ = prob.recover(r["lam"], r["p0"], f_s)
         du = None if u_prev is None else l2_diff(prob, u, u_prev)
         r.update(kind=kind, u=u, du=du, setup=S, prob=prob)
         out.append(r)
@@ -548,7 +556,9 @@ def picard_newton(levels, k, nu, beta, gamma, f_qp, dirichlet=None, eps_picard=1
                 kind = "newton"
             elif kind == "stokes":
                 kind = "picard"
-        winds = state_wind(prob, r["lam"], r["p0"], f_qp)
-        zs = local_states(prob, r["lam"], f_qp)
+        # the next linearisation at this step's fields (recovered with the
+        # load this step solved with)
+        winds = state_wind(prob, r["lam"], r["p0"], f_s)
+        zs = local_states(prob, r["lam"], f_s)
         lam, u_prev, p_prev = r["lam"], u, r["p0"]
     return out

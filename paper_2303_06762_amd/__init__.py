@@ -56,7 +56,8 @@ MAX_ALG3 = 128
 
 class Alg3Opts(ctypes.Structure):
     _fields_ = [("eps_picard", ctypes.c_double), ("newton_rtol", ctypes.c_double),
-                ("newton_atol", ctypes.c_double), ("max_picard", ctypes.c_int), ("max_newton", ctypes.c_int)]
+                ("newton_atol", ctypes.c_double), ("max_picard", ctypes.c_int), ("max_newton", ctypes.c_int),
+                ("dt_inv", ctypes.c_double)]
 
 
 class Alg3Info(ctypes.Structure):
@@ -569,13 +570,15 @@ def picard(solver, f_qp, steps, dirichlet=None):
 
 
 def picard_newton(solver, f_qp, dirichlet=None, eps_picard=1e-4, newton_rtol=1e-8, newton_atol=1e-10,
-                  max_picard=50, max_newton=20):
+                  max_picard=50, max_newton=20, dt_inv=0.0):
     """Alg. 3 on an opts.oseen Solver through hdgmg_picard_newton (the loop,
     its norms and the Picard -> Newton switch run in the library): a Stokes
     solve, Picard steps until ||u_n - u_{n-1}||_0 < eps_picard, then Newton
     steps until ||u_n - u_{n-1}||_0 <= max(newton_rtol ||u_n||_0,
-    newton_atol).  Returns a list of dicts (kind, u, p, state, info, status,
-    du) per solve, the fields copied in the library's per-step callback."""
+    newton_atol).  dt_inv > 0: the Stokes and Picard steps are backward-Euler
+    pseudo-time steps of size 1/dt_inv.  Returns a list of dicts (kind, u, p,
+    state, info, status, du) per solve, the fields copied in the library's
+    per-step callback."""
     torch = solver.torch
     if dirichlet is not None:
         solver.set_dirichlet(dirichlet)
@@ -591,7 +594,7 @@ def picard_newton(solver, f_qp, dirichlet=None, eps_picard=1e-4, newton_rtol=1e-
                         du=None if du < 0 else du, info=_info_dict(i)))
 
     cb = ALG3_STEP_FN(step)
-    a = Alg3Opts(eps_picard, newton_rtol, newton_atol, max_picard, max_newton)
+    a = Alg3Opts(eps_picard, newton_rtol, newton_atol, max_picard, max_newton, dt_inv)
     info = Alg3Info()
     solver._check(lib().hdgmg_picard_newton(solver._h, _ptr(f_qp), ctypes.byref(a), _ptr(u), _ptr(p), _ptr(state),
                                             ctypes.byref(info), cb, None), allow=(0, 1))

@@ -203,6 +203,7 @@ struct hdgmg_ctx {
   // Alg. 3 (hdgmg_picard_newton): previous velocity and state
   double* a3_u = nullptr;
   double* a3_state = nullptr;
+  double* a3_f = nullptr;     // pseudo-time load f + dt_inv u_{n-1}
   bool has_bd = false;
   // FGMRES basis: V [(restart+1)][N_skel], Z [restart][N_skel], scalars
   double *gm_V = nullptr, *gm_Z = nullptr, *gm_h = nullptr, *gm_y = nullptr, *gm_part = nullptr;
@@ -2347,9 +2348,27 @@ hdgmg_status hdgmg_picard_newton(hdgmg_ctx* ctx, const double* f_qp, const hdgmg
   const auto t0 = std::chrono::steady_clock::now();
   const DevLevel& KL = ctx->K;
   const long nqd = (long)KL.nc * ctx->Q.nq, ns = KL.ndof + KL.nc;
+  if (!(a->dt_inv >= 0.0) || !std::isfinite(a->dt_inv)) {
+    ctx->err = "hdgmg_picard_newton: dt_inv must be finite and >= 0";
+    return HDGMG_EINVAL;
+  }
   if (!ctx->a3_u) {
     TRY(dalloc(ctx, &ctx->a3_u, (size_t)nqd * 2));
     TRY(dalloc(ctx, &ctx->a3_state, (size_t)ns));
+  }
+  const bool ptime = a->dt_inv > 0.0;
+  if (ptime && !ctx->a3_f) TRY(dalloc(ctx, &ctx->a3_f, (size_t)nqd * 2));
+  const double beta0 = ctx->beta;
+  // pseudo-time steps (Stokes and Picard phases): mass term dt_inv u in the
+  // operator (beta + dt_inv at assembly) and dt_inv u_{n-1} in the load
+  struct BetaGuard {
+    hdgmg_ctx* c;
+    double b;
+    ~BetaGuard() { c->beta = b; }
+  } guard{ctx, beta0};
+  if (ptime) {
+    ctx->beta = beta0 + a->dt_inv;
+    launch_copy(ctx->st, nqd * 2, f_qp, ctx->a3_f);
   }
   if (info) std::memset(info, 0, sizeof(*info));
   TRY(hdgmg_set_wind(ctx, nullptr));
@@ -2359,7 +2378,8 @@ hdgmg_status hdgmg_picard_newton(hdgmg_ctx* ctx, const double* f_qp, const hdgmg
   while (true) {
     hdgmg_info inf;
     const bool warm = step > 0;
-    hdgmg_status s = hdgmg_solve_x0(ctx, f_qp, warm ? ctx->a3_state : nullptr,
+    const double* f_step = ptime && kind < 2 ? ctx->a3_f : f_qp;
+    hdgmg_status s = hdgmg_solve_x0(ctx, f_step, warm ? ctx->a3_state : nullptr,
                                     kind == 2 ? ctx->a3_state + KL.ndof : nullptr, u_qp, p_qp, state, &inf);
     if (s < 0) return s;
     result = std::max(result, s);
@@ -2397,6 +2417,13 @@ hdgmg_status hdgmg_picard_newton(hdgmg_ctx* ctx, const double* f_qp, const hdgmg
     // the next step linearises at this one
     launch_copy(ctx->st, nqd * 2, u_qp, ctx->a3_u);
     launch_copy(ctx->st, ns, state, ctx->a3_state);
+    if (ptime) {
+      if (kind < 2) {
+        launch_copy(ctx->st, nqd * 2, f_qp, ctx->a3_f);
+        launch_axpy(ctx->st, nqd * 2, a->dt_inv, ctx->a3_u, ctx->a3_f);
+      }
+      ctx->beta = kind < 2 ? beta0 + a->dt_inv : beta0;
+    }
     TRY(hdgmg_set_wind(ctx, ctx->a3_u));
     if (kind == 2) TRY(hdgmg_set_newton(ctx, ctx->a3_state));
     TRY(hdgmg_assemble(ctx));

@@ -134,6 +134,43 @@ def test_newton_solve(name):
     s.close()
 
 
+def test_alg3_pseudo_time_matches_oracle():
+    # backward-Euler pseudo-time steps in the Stokes and Picard phases
+    # (alg3 opts dt_inv), then steady Newton steps: the step kinds, every
+    # step's velocity and inner counts as the oracle's Alg. 3 with the same
+    # pseudo-time load and mass term
+    import paper_2303_06762_amd as hd
+    n, nr, k, nu, gamma, dt_inv = 2, 2, 2, 0.05, 1e2, 2.0
+    c, t = synth.kuhn_square(n)
+    levels = mesh.hierarchy(c, t, nr)
+    lv = levels[-1]
+    f = 0.5 * synth.source_uniform(7, 1, lv.n_cells, (k + 2) ** 2)[0]
+    lid_o = oseen.lid_dirichlet(lv, k)
+    _note("alg3 pseudo-time 128 cells k=2")
+    ref = oseen.picard_newton(levels, k, nu, 0.0, gamma, f, lid_o, eps_picard=1e-3, dt_inv=dt_inv)
+    s = hd.Solver(c, t, nr, k, 0.0, nu, gamma, oseen=1)
+    lid(s)
+    out = hd.picard_newton(s, dev(f), eps_picard=1e-3, dt_inv=dt_inv)
+    assert [o["kind"] for o in out] == [r["kind"] for r in ref]
+    for o_, r_ in zip(out, ref):
+        assert o_["status"] == 0
+        assert rel(host(o_["u"]), r_["u"]) < 1e-7
+        for a, b in zip(o_["info"]["its"], r_["its"]):
+            assert abs(a - b) <= 1, (o_["info"]["its"], r_["its"])
+    # the context's beta is restored: a plain solve afterwards equals a fresh context's
+    s2 = hd.Solver(c, t, nr, k, 0.0, nu, gamma, oseen=1)
+    lid(s2)
+    s2.assemble()
+    s.set_newton(None)
+    s.set_wind(None)
+    s.assemble()
+    u1 = host(s.solve(dev(f))[0])
+    u2 = host(s2.solve(dev(f))[0])
+    assert rel(u1, u2) < 1e-12
+    s.close()
+    s2.close()
+
+
 @pytest.mark.parametrize("paper_setting", [False, True])
 def test_alg3_matches_oracle(paper_setting):
     # default: (nu eps)^-1 = 1e2 with Uzawa to tolerance; paper setting:

@@ -127,3 +127,20 @@ def test_navier_stokes_convergence_order():
         errs.append(np.sqrt(np.sum(w[..., None] * (u - mf.velocity(X)) ** 2)))
     rate = np.log2(errs[0] / errs[1])
     assert rate > k + 1 - 0.3, errs
+
+
+def test_pseudo_time_picard_reaches_the_steady_solution():
+    # Sec. 5.2.2: backward-Euler pseudo-time steps in the Picard phase; at
+    # their fixed point the mass terms cancel, so Alg. 3 ends at the same
+    # discrete steady solution as without them
+    k = 2
+    levels, lv, nu, f, lid = cavity(k)
+    kw = dict(eps_picard=1e-3, direct=True, newton_rtol=1e-13, newton_atol=1e-14, max_newton=8)
+    ref = oseen.picard_newton(levels, k, nu, 0.0, 1e2, f, lid, **kw)
+    pt = oseen.picard_newton(levels, k, nu, 0.0, 1e2, f, lid, dt_inv=2.0, **kw)
+    assert pt[-1]["kind"] == "newton"
+    prob = pt[-1]["prob"]
+    un = oseen.l2_diff(prob, ref[-1]["u"], 0 * ref[-1]["u"])
+    assert oseen.l2_diff(prob, pt[-1]["u"], ref[-1]["u"]) <= 1e-10 * un
+    # the pseudo-time steps differ from plain Picard steps (the mass term acts)
+    assert oseen.l2_diff(prob, pt[1]["u"], ref[1]["u"]) > 1e-3 * un
