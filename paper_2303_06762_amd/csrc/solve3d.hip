@@ -1083,6 +1083,14 @@ hdgmg_status d3_assemble(Ctx3* c) {
     HIPC3(hipMemcpyAsync(c->K.S, c->cr[c->J - 1].S, (size_t)c->K.nc * 144 * sizeof(double),
                          hipMemcpyDeviceToDevice, c->st));
   HIPC3(hipStreamSynchronize(c->st));
+  // the host copies in dense row-major order (the device stores face row blocks)
+  for (int l = 0; l < c->J; ++l) {
+    std::vector<double> dense(hostB[l].size());
+    for (size_t cc = 0; cc < hostB[l].size() / 144; ++cc)
+      for (int r = 0; r < 12; ++r)
+        for (int q = 0; q < 12; ++q) dense[cc * 144 + r * 12 + q] = hostB[l][cc * 144 + sblk(r, q, 3, 12)];
+    hostB[l].swap(dense);
+  }
   // patch inverses
   if (c->k > 0) TRY3(patch_inverses(c, c->K));
   for (int l = 1; l < c->J; ++l) TRY3(patch_inverses(c, c->cr[l]));
@@ -1336,7 +1344,10 @@ hdgmg_status d3_export(const Ctx3* c, int what, int level, void* dst, size_t byt
     return HDGMG_EINVAL;
   }
   if (bytes < n) return HDGMG_EINVAL;
-  hipError_t e = hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToDevice, c->st);
+  // dense [nc][nK][nK] from the face-row-block storage
+  const DevLev3& D = what == 0 ? c->K : c->cr[level];
+  launch_blocks_to_dense(c->st, D.nc, 3 * D.mF, static_cast<const double*>(src), static_cast<double*>(dst));
+  hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(c->st);
   if (e != hipSuccess) {
     cc->err = std::string("HIP error: ") + hipGetErrorString(e);

@@ -559,7 +559,7 @@ __global__ void __launch_bounds__(NT) k_tet_local(TetCells E, int mode, int c0, 
     double* out = S + (long)cell * nK * nK;
     for (long e = tid; e < (long)nK * nK; e += NT) {
       const int rho = (int)(e / nK), lc = (int)(e % nK);
-      out[e] = 0.5 * (St[e] + St[(long)lc * nK + rho]);
+      out[sblk(rho, lc, 3 * mF, nK)] = 0.5 * (St[e] + St[(long)lc * nK + rho]);
     }
   } else if (mode == TET_LOAD) {
     for (int rho = tid; rho < d.nK; rho += NT) {
@@ -683,7 +683,7 @@ __global__ void k_cr_blocks3(const double* __restrict__ X, const int* __restrict
           const double gg = g[i][0] * g[j][0] + g[i][1] * g[j][1] + g[i][2] * g[j][2];
           double v = nuc * ff * gg * vol;
           if (aa == 0 && bb == 0) v += beta * q[i] * q[j] * Mrt[i][j] + eps_inv * q[i] * q[j] / vol;
-          out[(3 * i + aa) * 12 + 3 * j + bb] = v;
+          out[sblk(3 * i + aa, 3 * j + bb, 3, 12)] = v;
         }
 }
 
@@ -703,10 +703,20 @@ __global__ void __launch_bounds__(64) k_cell_apply3(Level3View<TS> L, const doub
     for (int i = 0; i < 4; ++i) dx += L.cdiv[4 * c + i] * xs[i * m3];
   for (int row = lane; row < nK; row += 64) {
     double acc = 0.0;
-    for (int col = 0; col < nK; ++col) acc += (double)Sc[(long)col * nK + row] * xs[col];
+    const TS* Sr = Sc + (long)(row / m3) * m3 * nK + row % m3;  // row's face block
+    for (int col = 0; col < nK; ++col) acc += (double)Sr[(long)col * m3] * xs[col];
     if (L.al > 0.0 && row % m3 == 0) acc += L.al / L.vol[c] * L.cdiv[4 * c + row / m3] * dx;
     yK[(long)c * nK + row] = acc;
   }
+}
+
+__global__ void k_blocks_to_dense(int nc, int m3, const double* __restrict__ in, double* __restrict__ out) {
+  const int nK = 4 * m3;
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)nc * nK * nK) return;
+  const long c = t / ((long)nK * nK);
+  const int e = (int)(t % ((long)nK * nK)), r = e / nK, q = e % nK;
+  out[t] = in[c * nK * nK + sblk(r, q, m3, nK)];
 }
 
 __global__ void k_f32_blocks_noal(int nc, int mF, const double* __restrict__ S, const double* __restrict__ cdiv,
@@ -715,7 +725,8 @@ __global__ void k_f32_blocks_noal(int nc, int mF, const double* __restrict__ S, 
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (long)nc * nK * nK) return;
   const int c = (int)(t / ((long)nK * nK)), e = (int)(t % ((long)nK * nK));
-  const int r = e / nK, q = e % nK;
+  // storage position e of the sblk layout -> entry (r, q)
+  const int r = e / (m3 * nK) * m3 + e % m3, q = (e % (m3 * nK)) / m3;
   double v = S[t];
   if (r % m3 == 0 && q % m3 == 0) v -= al / vol[c] * cdiv[4 * c + r / m3] * cdiv[4 * c + q / m3];
   out[t] = (float)v;
@@ -771,7 +782,8 @@ __global__ void __launch_bounds__(NT) k_patch_inverse3(Level3View<double> L, con
   for (int ci = 0; ci < ncl; ++ci) {
     const double* Sc = L.S + (long)pc[c0 + ci] * nK * nK;
     for (long e = tid; e < (long)nK * nK; e += NT) {
-      const int r = (int)(e / nK), c = (int)(e % nK);
+      // storage position e of the sblk layout -> entry (r, c)
+      const int r = (int)(e / ((long)m3 * nK)) * m3 + (int)(e % m3), c = (int)((e % ((long)m3 * nK)) / m3);
       const int sr = slot[ci][r / m3], sc = slot[ci][c / m3];
       if (sr < 0 || sc < 0) continue;
       A[(long)(sr * m3 + r % m3) * w + sc * m3 + c % m3] += Sc[e];
@@ -856,20 +868,21 @@ __global__ void __launch_bounds__(BS) k_patch_gs3(Level3View<TS> L, const int* _
       }
     if (i < 0) continue;
     const int cell = cellid[ci];
-    const TS* Sc = L.S + (long)cell * nK * nK + i * m3 + rr;
+    // face i's row block: rows contiguous, columns m3 apart
+    const TS* Sc = L.S + (long)cell * nK * nK + (long)i * m3 * nK + rr;
     const double* xc = xs[ci];
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     int col = 0;
     for (; col + 8 <= nK; col += 8) {
       double v[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = (double)Sc[(long)(col + u) * nK];
+      for (int u = 0; u < 8; ++u) v[u] = (double)Sc[(long)(col + u) * m3];
       a0 += v[0] * xc[col] + v[4] * xc[col + 4];
       a1 += v[1] * xc[col + 1] + v[5] * xc[col + 5];
       a2 += v[2] * xc[col + 2] + v[6] * xc[col + 6];
       a3 += v[3] * xc[col + 3] + v[7] * xc[col + 7];
     }
-    for (; col < nK; ++col) a0 += (double)Sc[(long)col * nK] * xc[col];
+    for (; col < nK; ++col) a0 += (double)Sc[(long)col * m3] * xc[col];
     double acc = (a0 + a1) + (a2 + a3);
     if (L.al > 0.0 && rr == 0) {
       double dx = 0.0;
@@ -994,6 +1007,12 @@ void launch_cell_apply3(hipStream_t st, Level3View<TS> L, const double* x, doubl
 }
 template void launch_cell_apply3<double>(hipStream_t, Level3View<double>, const double*, double*);
 template void launch_cell_apply3<float>(hipStream_t, Level3View<float>, const double*, double*);
+
+void launch_blocks_to_dense(hipStream_t st, int nc, int m3, const double* in, double* out) {
+  const long n = (long)nc * 16 * m3 * m3;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_blocks_to_dense, dim3(blocks(n, 256)), dim3(256), 0, st, nc, m3, in, out);
+}
 
 void launch_face_gather3(hipStream_t st, int nint, int mF, int nK, const int* fcell, const int* floc,
                          const double* yK, double alpha, const double* b, double* y) {

@@ -63,6 +63,12 @@ HDI Dims3 dims3(int k) {
   return d;
 }
 
+// Storage of a symmetric cell block (nK = 4 m3 unknowns, m3 per face): by
+// face row blocks -- the m3 rows of local face f form an m3 x nK
+// column-major block at offset f m3 nK -- so that the rows of one face, the
+// unit a patch sweep reads, are one contiguous run.  Entry (r, c):
+HDI long sblk(int r, int c, int m3, int nK) { return (long)(r / m3) * m3 * nK + (long)c * m3 + r % m3; }
+
 // Reference rules (device memory, read through a pointer).
 struct TetTables {
   int k, nq, nfq;
@@ -80,7 +86,8 @@ struct Level3View {
   const int* cell_dofs;  // [nc][4] interior face id or -1
   const int* fcell;      // [nint][2] cells of each interior face
   const int* floc;       // [nint][2] local face index in those cells
-  const TS* S;           // [nc][nK][nK] symmetric cell blocks of A^eps, or of A
+  const TS* S;           // [nc][nK * nK] symmetric cell blocks of A^eps, or of A,
+                         // entry (r, c) of cell K at K nK^2 + sblk(r, c, m3, nK)
                          // (al > 0: the AL term is added apart, in FP64)
   // AL term eps^-1 |K|^-1 d d^T applied apart when al > 0: d_i = cdiv[4K+i]
   // on the mode-0 normal unknown of local face i
@@ -92,7 +99,7 @@ struct Level3View {
 enum { TET_CONDENSE = 0, TET_LOAD = 1, TET_RECOVER = 2 };
 
 // Element kernels, a workgroup per cell of [c0, c0 + nb): TET_CONDENSE
-// writes S (+ AL term) [nc][nK][nK]; TET_LOAD writes gK [nc][nK] from
+// writes S (+ AL term) [nc][nK * nK] (sblk layout); TET_LOAD writes gK [nc][nK] from
 // f [nc][nq][3]; TET_RECOVER reads lam (skeleton) and p0 [nc] and writes
 // u [nc][nq][3], p [nc][nq].  ws: tet_ws_words(k, mode) doubles per cell of
 // the batch.  status bit 1: a singular local system.
@@ -110,7 +117,8 @@ struct TetCells {
 void launch_tet_local(hipStream_t st, const TetCells& E, int mode, int c0, int nb, double* ws, const double* f,
                       const double* lam, const double* p0, double* S, double* gK, double* u, double* p,
                       int* status);
-// Closed-form lowest-order blocks [nc][12][12] (k0-stOptForm on tetrahedra).
+// Closed-form lowest-order blocks [nc][144] (k0-stOptForm on tetrahedra;
+// sblk layout with m3 = 3).
 void launch_cr_blocks3(hipStream_t st, const double* X, const int* cells, int nc, const double* nu_cells,
                        double beta, double eps_inv, double* A);
 // yK = S_K x_K for every cell (a wavefront per cell), then y = alpha * (sum
@@ -143,6 +151,8 @@ void launch_uzawa_rhs3(hipStream_t st, int nint, int mF, const double* g, const 
                        const double* p0, double* b);
 void launch_uzawa_update3(hipStream_t st, int nc, int mF, const int* cell_dofs, const double* cdiv,
                           const double* vol, const double* lam, double eps_inv, double* p0, double* part, int nb);
+// Cell blocks from the sblk layout to dense [nc][nK][nK] (row-major).
+void launch_blocks_to_dense(hipStream_t st, int nc, int m3, const double* in, double* out);
 // out[i] = (float) in[i]
 void launch_f32_copy(hipStream_t st, long n, const double* in, float* out);
 // FP32 copy of cell blocks without their AL term: out = S - al |K|^-1 d d^T
