@@ -349,16 +349,27 @@ class Problem:
             us.append(u), ps.append(p), Ls.append(L), ds.append(dv)
         return np.array(us), np.array(ps), np.array(Ls), np.array(ds)
 
+    def constraint_rhs(self):
+        """-D lambda equals this per cell (the prescribed boundary flux; zero
+        for homogeneous data)."""
+        return np.zeros(self.lv.n_cells)
+
     def solve_direct(self, f_qp):
         """R1: the condensed saddle point [[A, -D^T, 0], [-D, 0, w], [0, w^T, 0]]
-        with w_K = |K| (mean-free pressure), by sparse LU.  Returns
-        (lambda, p0 [n_cells])."""
+        with w_K = |K| (mean-free pressure), by sparse LU; with do-nothing
+        facets the pressure is determined and [[A, -D^T], [-D, 0]] is
+        solved.  Returns (lambda, p0 [n_cells])."""
         A = self.matrix_A()
         D = self.matrix_D()
-        w = sp.csr_matrix(self.lv.area.reshape(-1, 1))
         nK = self.lv.n_cells
-        Kmat = sp.bmat([[A, -D.T, None], [-D, None, w], [None, w.T, None]], format="csc")
-        rhs = np.concatenate([self.rhs(f_qp), np.zeros(nK + 1)])
+        c = self.constraint_rhs()
+        if getattr(self.lv, "outflow", None) is not None and self.lv.outflow.any():
+            Kmat = sp.bmat([[A, -D.T], [-D, None]], format="csc")
+            rhs = np.concatenate([self.rhs(f_qp), c])
+        else:
+            w = sp.csr_matrix(self.lv.area.reshape(-1, 1))
+            Kmat = sp.bmat([[A, -D.T, None], [-D, None, w], [None, w.T, None]], format="csc")
+            rhs = np.concatenate([self.rhs(f_qp), c, [0.0]])
         sol = spla.spsolve(Kmat, rhs)
         return sol[:self.n_dof], sol[self.n_dof:self.n_dof + nK]
 

@@ -52,18 +52,22 @@ def fcg(A, b, prec, rtol=1e-8, atol=1e-10, max_it=500, x0=None):
     return x, it, hist
 
 
-def uzawa(Aeps, D, area, g, eps_inv, inner, max_steps=50, tol=1e-10):
+def uzawa(Aeps, D, area, g, eps_inv, inner, max_steps=50, tol=1e-10, flux_b=None):
     """AL-Uzawa.  inner(b) -> (lambda, its, hist).  Stops when
-    ||p^n - p^{n-1}||_{L2} <= tol * max(1, ||p^n||_{L2}) or after max_steps.
+    ||p^n - p^{n-1}||_{L2} <= tol * max(1, ||p^n||_{L2}) or after max_steps
+    (tol < 0: exactly max_steps).  flux_b: per-cell flux of prescribed
+    normal boundary values (the constraint is D lambda + flux_b = 0).
     Returns (lambda, p0, list of (its, hist))."""
     p = np.zeros(D.shape[0])
+    fb = np.zeros(D.shape[0]) if flux_b is None else flux_b
+    g = g - eps_inv * (D.T @ (fb / area))
     log = []
     lam = None
     for n in range(max_steps):
         b = g + D.T @ p
         lam, its, hist = inner(b)
         log.append((its, hist))
-        dp = -eps_inv * (D @ lam) / area
+        dp = -eps_inv * (D @ lam + fb) / area
         p = p + dp
         dn = np.sqrt(np.sum(area * dp ** 2))
         pn = np.sqrt(np.sum(area * p ** 2))

@@ -6,8 +6,12 @@ Conventions (Sec. 2 and Sec. 3.4.2 of the paper; the numbering is ours):
   lexicographic order of that pair.  Facet frame: t_F = (x_v1 - x_v0)/|.|,
   n_F = (t_y, -t_x); a facet point has parameter s in [0,1] from v0 to v1.
   sigma_{K,F} = n_{K,F} . n_F = +-1 with n_{K,F} the outward normal.
-* Interior facets (two adjacent cells) are numbered in facet order; boundary
-  facets carry no unknowns (homogeneous Dirichlet data).
+* Interior facets (two adjacent cells) and do-nothing (outflow) boundary
+  facets carry the skeleton unknowns and are numbered together in facet
+  order ("dof facets", int_id); the other boundary facets carry Dirichlet
+  data (homogeneous unless given).  outflow: the coarsest mesh's do-nothing
+  facets as vertex pairs; on refinement both halves of such a facet are
+  do-nothing facets.
 * Red refinement: the midpoint of coarse facet e becomes vertex nv + e; cell
   c = (a, b, c) has children 4c+0 = (a, m_ab, m_ca), 4c+1 = (m_ab, b, m_bc),
   4c+2 = (m_ca, m_bc, c), 4c+3 = (m_bc, m_ca, m_ab).
@@ -18,7 +22,7 @@ import numpy as np
 class Level:
     """One triangulation with its skeleton."""
 
-    def __init__(self, coords, cells):
+    def __init__(self, coords, cells, outflow=None):
         self.coords = np.asarray(coords, dtype=np.float64)
         self.cells = np.asarray(cells, dtype=np.int64)
         nc = len(self.cells)
@@ -46,9 +50,17 @@ class Level:
                 self.facet_local[e, fill[e]] = i
                 fill[e] += 1
         self.interior = cnt == 2
+        self.outflow = np.zeros(ne, dtype=bool)
+        if outflow is not None and len(outflow):
+            key = {(int(min(a, b)), int(max(a, b))) for a, b in outflow}
+            for e in range(ne):
+                if cnt[e] == 1 and (int(edges[e, 0]), int(edges[e, 1])) in key:
+                    self.outflow[e] = True
+            assert self.outflow.sum() == len(key), "outflow pairs must be boundary facets"
+        self.dof = self.interior | self.outflow
         self.int_id = -np.ones(ne, dtype=np.int64)
-        self.int_id[self.interior] = np.arange(int(self.interior.sum()))
-        self.n_int = int(self.interior.sum())
+        self.int_id[self.dof] = np.arange(int(self.dof.sum()))
+        self.n_int = int(self.dof.sum())
         X0 = self.coords[edges[:, 0]]
         X1 = self.coords[edges[:, 1]]
         d = X1 - X0
@@ -71,10 +83,10 @@ class Level:
         self.n_vertices = nv
 
     def vertex_facets(self):
-        """For each vertex, the interior facets containing it (sorted)."""
+        """For each vertex, the dof facets containing it (sorted)."""
         out = [[] for _ in range(self.n_vertices)]
         for e in range(self.n_facets):
-            if self.interior[e]:
+            if self.dof[e]:
                 out[self.edges[e, 0]].append(e)
                 out[self.edges[e, 1]].append(e)
         return [sorted(x) for x in out]
@@ -160,14 +172,28 @@ def refine(coords, cells):
     return new, out, parent
 
 
-def hierarchy(coords, cells, n_refine):
-    """Levels T_1 (coarsest) .. T_J, J = n_refine + 1, with parent maps."""
-    levels = [Level(coords, cells)]
+def refine_pairs(lvl, pairs):
+    """Both halves of each facet (a, b) of lvl after red refinement."""
+    out = []
+    nv = len(lvl.coords)
+    for a, b in pairs:
+        a, b = int(min(a, b)), int(max(a, b))
+        e = int(np.where((lvl.edges[:, 0] == a) & (lvl.edges[:, 1] == b))[0][0])
+        out += [(a, nv + e), (b, nv + e)]
+    return out
+
+
+def hierarchy(coords, cells, n_refine, outflow=None):
+    """Levels T_1 (coarsest) .. T_J, J = n_refine + 1, with parent maps;
+    outflow: do-nothing facets of the coarsest mesh (vertex pairs)."""
+    levels = [Level(coords, cells, outflow)]
     parents = [None]
     c, t = np.asarray(coords, float), np.asarray(cells)
+    pairs = list(outflow) if outflow is not None else []
     for _ in range(n_refine):
+        pairs = refine_pairs(levels[-1], pairs)
         c, t, p = refine(c, t)
-        levels.append(Level(c, t))
+        levels.append(Level(c, t, pairs))
         parents.append(p)
     for l, p in zip(levels, parents):
         l.parent = p

@@ -95,7 +95,7 @@ def averaging(lc, lf):
             out.append((2 * ei + 1, phi * lc.tangent[E]))
         return out, lam
 
-    for F in np.where(lf.interior)[0]:
+    for F in np.where(lf.dof)[0]:
         fi = lf.int_id[F]
         x = lf.midpoint[F]
         Kf = lf.facet_cells[F, 0]
@@ -106,11 +106,15 @@ def averaging(lc, lf):
         if lam.min() < 1e-12:
             i0 = int(np.argmin(lam))
             E = lc.cell_facets[T, i0]
-            assert lc.interior[E], "fine interior facet on a coarse boundary facet"
-            a, b = lc.facet_cells[E]
-            T2 = b if a == T else a
-            w2, _ = cr_value_weights(T2, x)
-            w = [(d, 0.5 * v) for d, v in w] + [(d, 0.5 * v) for d, v in w2]
+            if lc.interior[E]:
+                # the mean of the two sides on a coarse interior facet
+                a, b = lc.facet_cells[E]
+                T2 = b if a == T else a
+                w2, _ = cr_value_weights(T2, x)
+                w = [(d, 0.5 * v) for d, v in w] + [(d, 0.5 * v) for d, v in w2]
+            else:
+                # a fine do-nothing facet on a coarse one: the one side
+                assert lc.outflow[E], "fine dof facet on a coarse Dirichlet facet"
         for d, v in w:
             rows += [2 * fi, 2 * fi + 1]
             cols += [d, d]

@@ -223,7 +223,10 @@ def zero_wind(X):
 class OseenProblem(hdg.Problem):
     """Condensed Picard-linearised system on one level.  winds: one callable
     per cell (None: no convection).  dirichlet: [n_facets, k+1] tangential
-    coefficients on boundary facets (None: homogeneous).  transpose: the
+    coefficients on the Dirichlet boundary facets, or [n_facets, 2, k+1]
+    normal and tangential ones (an inflow); None: homogeneous.  Prescribed
+    normal values change the cells' divergence by their flux (flux_b), which
+    the AL-Uzawa loop and the direct solve carry.  transpose: the
     transposed system (convection matrices transposed per cell)."""
 
     def __init__(self, lv, k, nu, beta, gamma, winds=None, dirichlet=None, transpose=False, newton_z=None):
@@ -245,12 +248,25 @@ class OseenProblem(hdg.Problem):
         if self.dirichlet is None:
             return out
         lv = self.lv
+        full = np.ndim(self.dirichlet) == 3
         for f in range(3):
             E = lv.cell_facets[K, f]
             if lv.int_id[E] < 0:
                 for j in range(self.m):
-                    out[hdg.lam_index(self.k, f, 1, j)] = self.dirichlet[E, j]
+                    if full:
+                        out[hdg.lam_index(self.k, f, 0, j)] = self.dirichlet[E, 0, j]
+                        out[hdg.lam_index(self.k, f, 1, j)] = self.dirichlet[E, 1, j]
+                    else:
+                        out[hdg.lam_index(self.k, f, 1, j)] = self.dirichlet[E, j]
         return out
+
+    def flux_b(self):
+        """Per cell |K| div of the prescribed boundary values: d . (boundary
+        part of the local skeleton vector), [n_cells]."""
+        return np.array([e.d @ self.boundary_local(K) for K, e in enumerate(self.elems)])
+
+    def constraint_rhs(self):
+        return self.flux_b()
 
     def rhs(self, f_qp):
         g = np.zeros(self.n_dof)
@@ -450,11 +466,14 @@ class OseenSetup:
         lam = np.zeros(self.prob.n_dof) if lam0 is None else lam0.copy()
         log = []
         area = self.lv.area
+        fb = self.prob.flux_b()
+        # the AL term of the prescribed flux: A^eps lam = g + D^T p - eps^-1 D^T (flux_b / |K|)
+        g = g - self.eps_inv * (self.D.T @ (fb / area))
         for n in range(uzawa_max):
             b = g + self.D.T @ p
             lam, its, hist = fgmres(self.Aeps, b, self.prec, rtol, atol, max_it, lam, self.restart)
             log.append((its, hist))
-            dp = -self.eps_inv * (self.D @ lam) / area
+            dp = -self.eps_inv * (self.D @ lam + fb) / area
             p = p + dp
             dn = np.sqrt(np.sum(area * dp ** 2))
             pn = np.sqrt(np.sum(area * p ** 2))

@@ -8,16 +8,25 @@ R2: the method: AL-Uzawa outer loop (stOpEq-ALU), flexible CG inner solve
 """
 import numpy as np
 
-from . import mesh, hdg, mg, krylov
+from . import mesh, hdg, mg, krylov, oseen
 
 
 class Setup:
     def __init__(self, coords, cells, n_refine, k, nu, beta, gamma,
-                 m_p=1, m_h=1, q=1, growth=2, harmonic=True, smoother="gs", additive=False):
-        self.levels = mesh.hierarchy(coords, cells, n_refine)
+                 m_p=1, m_h=1, q=1, growth=2, harmonic=True, smoother="gs", additive=False,
+                 outflow=None, dirichlet=None):
+        """outflow: do-nothing facets of the coarsest mesh (vertex pairs);
+        dirichlet: boundary data on the finest level as in
+        oseen.OseenProblem (a callable lv -> array is evaluated there)."""
+        self.levels = mesh.hierarchy(coords, cells, n_refine, outflow)
         self.lv = self.levels[-1]
         self.k = k
-        self.prob = hdg.Problem(self.lv, k, nu, beta, gamma)
+        if callable(dirichlet):
+            dirichlet = dirichlet(self.lv)
+        if dirichlet is not None or outflow is not None:
+            self.prob = oseen.OseenProblem(self.lv, k, nu, beta, gamma, None, dirichlet)
+        else:
+            self.prob = hdg.Problem(self.lv, k, nu, beta, gamma)
         self.Aeps = self.prob.matrix_Aeps().tocsr()
         self.D = self.prob.matrix_D().tocsr()
         self.eps_inv = self.prob.eps_inv
@@ -32,5 +41,5 @@ class Setup:
         g = self.prob.rhs(f_qp)
         lam, p0, log = krylov.uzawa(self.Aeps, self.D, self.lv.area, g, self.eps_inv,
                                     lambda b: self.inner(b, rtol, atol, max_it),
-                                    uzawa_max, uzawa_tol)
+                                    uzawa_max, uzawa_tol, self.prob.constraint_rhs())
         return dict(g=g, lam=lam, p0=p0, its=[l[0] for l in log], hist=[l[1] for l in log])

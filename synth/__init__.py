@@ -110,6 +110,62 @@ def lid_velocity(ends, top=1.0):
     return g
 
 
+def step_domain(n=1, length=4.0, step=True):
+    """The backward-facing step ([0.5, L] x [0, 0.5]) u ([0, L] x [0.5, 1])
+    of the paper's Sec. 5.3 (L = 4) from squares of side 0.5/n, each split
+    along its (i,j)-(i+1,j+1) diagonal as in kuhn_square; vertices are the
+    used grid points (i, j) in (j, i) lexicographic order.  step=False: the
+    channel [0, L] x [0.5, 1] alone.  Returns (coords, cells, outflow):
+    outflow lists the vertex pairs of the facets on x = L (the do-nothing
+    boundary)."""
+    h = 0.5 / n
+    ni, nj = int(round(length / h)), 2 * n
+    sq = [(i, j) for j in range(nj) for i in range(ni) if not ((i < n or not step) and j < n)]
+    used = set()
+    for i, j in sq:
+        used |= {(i, j), (i + 1, j), (i, j + 1), (i + 1, j + 1)}
+    order = sorted(used, key=lambda v: (v[1], v[0]))
+    idx = {v: a for a, v in enumerate(order)}
+    coords = np.array([(i * h, j * h) for i, j in order], dtype=np.float64)
+    cells = []
+    for i, j in sq:
+        cells.append((idx[i, j], idx[i + 1, j], idx[i + 1, j + 1]))
+        cells.append((idx[i, j], idx[i, j + 1], idx[i + 1, j + 1]))
+    outflow = [(idx[ni, j], idx[ni, j + 1]) for j in range(0 if step else n, nj)]
+    return coords, np.asarray(cells, dtype=np.int32), outflow
+
+
+def boundary_coefficients(ends, k, velocity):
+    """Normal and tangential coefficients [n_facets][2][k+1] of a boundary
+    velocity field: the facet L^2 projection of velocity(X) . n_F and
+    . t_F onto the modes phi_j(s) = sqrt(2j+1) P_j(2s-1), s from the first
+    end point to the second, t_F = (second - first)/|.|, n_F = (t_y, -t_x).
+    velocity maps points [..., 2] to vectors [..., 2]; ends [nb][2][2]."""
+    ends = np.asarray(ends, dtype=np.float64)
+    xg, wg = np.polynomial.legendre.leggauss(k + 4)
+    s, w = 0.5 * (xg + 1.0), 0.5 * wg
+    phi = np.stack([np.sqrt(2 * j + 1) * np.polynomial.legendre.legval(2 * s - 1, np.eye(k + 1)[j])
+                    for j in range(k + 1)])
+    out = np.zeros((ends.shape[0], 2, k + 1))
+    for i, (a, b) in enumerate(ends):
+        t = (b - a) / np.hypot(*(b - a))
+        nrm = np.array([t[1], -t[0]])
+        X = a[None, :] + s[:, None] * (b - a)[None, :]
+        u = velocity(X)
+        out[i, 0] = phi @ (w * (u @ nrm))
+        out[i, 1] = phi @ (w * (u @ t))
+    return out
+
+
+def step_inflow(X, x0=0.0):
+    """The paper's inflow (16 (1 - y)(y - 0.5), 0) on x = x0 (zero elsewhere)."""
+    X = np.asarray(X)
+    on = np.abs(X[..., 0] - x0) < 1e-12
+    u = np.zeros(X.shape)
+    u[..., 0] = np.where(on, 16.0 * (1.0 - X[..., 1]) * (X[..., 1] - 0.5), 0.0)
+    return u
+
+
 def lid_coefficients(ends, k, profile, top=1.0):
     """Tangential boundary coefficients [n_boundary_facets][k+1] of the lid
     velocity (profile(x), 0) on the facets of the side y = top (zero
