@@ -76,6 +76,18 @@ typedef struct {
   int n_cells;
   const int32_t* cells;    /* host, [n_cells][3] vertex indices            */
   int n_refine;            /* J = n_refine + 1 levels                      */
+  int n_outflow;           /* do-nothing (outflow) facets of T_1 (Sec. 5.3:
+                              (nu grad u - p I) n = 0 holds weakly there);
+                              0 for none.  Both halves of such a facet are
+                              do-nothing facets on the next level.  They
+                              carry skeleton unknowns (both components)
+                              like interior facets; with any of them the
+                              pressure is determined (no mean-free
+                              normalisation) and the preconditioner runs
+                              its launch-per-colour kernels on every level.
+                              Triangular meshes only.                    */
+  const int32_t* outflow;  /* host, [n_outflow][2] vertex pairs of boundary
+                              facets of T_1 (EMESH if a pair is not one)   */
 } hdgmg_mesh;
 
 /* Solver options (Alg. 1 / Alg. 2 parameters and stopping rules, Sec. 5). */
@@ -428,6 +440,17 @@ hdgmg_status hdgmg_picard_newton(hdgmg_ctx* ctx, const double* f_qp, const hdgmg
                                  double* p_qp, double* state, hdgmg_alg3_info* info,
                                  hdgmg_alg3_step_fn step_fn, void* step_ctx);
 
+/* Normal and tangential Dirichlet data on the Dirichlet boundary facets (an
+ * inflow, Sec. 5.3): uhat_b device [n_boundary_facets][2][k+1] (facet
+ * order of hdgmg_export what 3; component 0 the normal coefficients c^n
+ * along n_F = (t_y, -t_x), 1 the tangential ones, modes as the skeleton's),
+ * NULL: homogeneous.  The prescribed normal values enter the cells'
+ * divergence: hdgmg_solve imposes div u_h = 0 with their flux included
+ * (the AL-Uzawa update and the load's AL term carry it).  Without
+ * do-nothing facets the data must have zero net flux.  Generalized Stokes
+ * contexts only (ESTATE with opts.oseen).  Triangular meshes only. */
+hdgmg_status hdgmg_set_dirichlet_full(hdgmg_ctx* ctx, const double* uhat_b);
+
 /* Tangential Dirichlet data given as one constant velocity per boundary
  * facet, g_b device [n_boundary_facets][2] (facet order, hdgmg_export what
  * 3): the library sets uhat . t_F = g_b . t_F (mode 0; the exact facet L^2
@@ -505,7 +528,8 @@ hdgmg_status hdgmg_query(const hdgmg_ctx* ctx, int what, int level, int64_t* val
  *           [n_cells(level)][6][6]
  *   what 2: coordinates of the data points of the finest cells
  *           [n_cells][n_q][2]
- *   what 3: end points of the finest boundary facets, in facet order,
+ *   what 3: end points of the finest (Dirichlet) boundary facets -- every
+ *           boundary facet but the do-nothing ones -- in facet order,
  *           [n_boundary_facets][2][2] (vertex v0 < v1 first: t_F points
  *           from the first to the second)
  *   what 4: data-rule weights times cell areas, w_q |K|, [n_cells][n_q]

@@ -25,7 +25,8 @@ MAX_UZAWA = 64
 class Mesh(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("n_vertices", ctypes.c_int),
                 ("coords", ctypes.POINTER(ctypes.c_double)), ("n_cells", ctypes.c_int),
-                ("cells", ctypes.POINTER(ctypes.c_int32)), ("n_refine", ctypes.c_int)]
+                ("cells", ctypes.POINTER(ctypes.c_int32)), ("n_refine", ctypes.c_int),
+                ("n_outflow", ctypes.c_int), ("outflow", ctypes.POINTER(ctypes.c_int32))]
 
 
 class Opts(ctypes.Structure):
@@ -108,7 +109,7 @@ class HdgmgError(RuntimeError):
 
 SYMBOLS = ["hdgmg_default_opts", "hdgmg_setup", "hdgmg_assemble", "hdgmg_solve",
            "hdgmg_solve_adjoint", "hdgmg_solve_x0", "hdgmg_set_wind", "hdgmg_set_newton", "hdgmg_set_dirichlet",
-           "hdgmg_set_dirichlet_velocity", "hdgmg_picard_newton", "hdgmg_postprocess",
+           "hdgmg_set_dirichlet_velocity", "hdgmg_set_dirichlet_full", "hdgmg_picard_newton", "hdgmg_postprocess",
            "hdgmg_solve_batch", "hdgmg_solve_adjoint_batch",
            "hdgmg_rhs",
            "hdgmg_apply", "hdgmg_precondition", "hdgmg_inner_solve", "hdgmg_inner_solve_noalloc", "hdgmg_recover",
@@ -141,7 +142,8 @@ def lib():
     L.hdgmg_picard_newton.restype = i32
     L.hdgmg_solve_x0.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(Info)]
     L.hdgmg_solve_x0.restype = i32
-    for name in ("hdgmg_set_wind", "hdgmg_set_newton", "hdgmg_set_dirichlet", "hdgmg_set_dirichlet_velocity"):
+    for name in ("hdgmg_set_wind", "hdgmg_set_newton", "hdgmg_set_dirichlet", "hdgmg_set_dirichlet_velocity",
+                 "hdgmg_set_dirichlet_full"):
         getattr(L, name).argtypes = [vp, vp]
         getattr(L, name).restype = i32
     for name in ("hdgmg_rhs", "hdgmg_apply", "hdgmg_precondition"):
@@ -193,17 +195,19 @@ class Solver:
     solve(f) -> (u, p).  Tensors are torch float64 CUDA tensors."""
 
     def __init__(self, coords, cells, n_refine, k, beta, nu, gamma, opts=None, stream=None, allocator="torch",
-                 **kw):
+                 outflow=None, **kw):
         import torch
         self.torch = torch
         L = lib()
         coords = np.ascontiguousarray(coords, dtype=np.float64)
         cells = np.ascontiguousarray(cells, dtype=np.int32)
         nu = np.ascontiguousarray(np.atleast_1d(np.asarray(nu, dtype=np.float64)))
-        self._keep = (coords, cells, nu)
+        out = np.ascontiguousarray(np.asarray(outflow if outflow is not None else np.zeros((0, 2)), dtype=np.int32))
+        self._keep = (coords, cells, nu, out)
         self.dim = int(coords.shape[1])
         m = Mesh(self.dim, len(coords), coords.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                 len(cells), cells.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), int(n_refine))
+                 len(cells), cells.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), int(n_refine),
+                 len(out), out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if len(out) else None)
         if opts is None:
             opts = default_opts(**kw)
         self.opts = opts
@@ -398,6 +402,12 @@ class Solver:
         out = self.torch.empty((max(nb, 1), 2, 2), dtype=self.torch.float64, device="cuda")
         self._check(lib().hdgmg_export(self._h, 3, 0, _ptr(out), out.numel() * 8))
         return out[:nb]
+
+    def set_dirichlet_full(self, uhat_b):
+        """hdgmg_set_dirichlet_full: normal and tangential coefficients
+        [n_boundary_facets][2][k+1] (None: homogeneous)."""
+        self._check(lib().hdgmg_set_dirichlet_full(self._h, ctypes.c_void_p(None) if uhat_b is None
+                                                   else _ptr(uhat_b.contiguous())))
 
     def set_dirichlet_velocity(self, g_b):
         """hdgmg_set_dirichlet_velocity: tangential data from one constant

@@ -117,7 +117,7 @@ __global__ void __launch_bounds__(WL) k_condense_wave(ElemLevel E, double* __res
     for (int e = lane; e < 3 * m; e += WL) {
       const int i = e / m, j = e % m;
       const int d = E.cell_dofs[3 * c + i];
-      tp[e] = d >= 0 ? E.nw_lam[((long)d * 2 + 1) * m + j] : (E.bdl ? E.bdl[((long)c * 3 + i) * m + j] : 0.0);
+      tp[e] = d >= 0 ? E.nw_lam[((long)d * 2 + 1) * m + j] : (E.bdl ? E.bdl[(((long)c * 3 + i) * 2 + 1) * m + j] : 0.0);
     }
   }
   if (lane == 0) sing = 0;

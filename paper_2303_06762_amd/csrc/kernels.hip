@@ -34,7 +34,8 @@ __device__ inline void boundary_local(const ElemLevel& E, int c, double* lb) {
   for (int i = 0; i < 6 * m; ++i) lb[i] = 0.0;
   if (!E.bdl) return;
   for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < m; ++j) lb[(i * 2 + 1) * m + j] = E.bdl[((long)c * 3 + i) * m + j];
+    for (int cc = 0; cc < 2; ++cc)
+      for (int j = 0; j < m; ++j) lb[(i * 2 + cc) * m + j] = E.bdl[(((long)c * 3 + i) * 2 + cc) * m + j];
 }
 
 __global__ void k_load(ElemLevel E, int c0, int nbatch, const double* __restrict__ f, double* ws, double* gK,
@@ -200,14 +201,26 @@ __global__ void k_facet_flux(QuadTables Q, const double* __restrict__ X, const i
   flux[fi] = s_ * g.len[i];
 }
 
-__global__ void k_bd_local(int nc, int m, const int* __restrict__ cbf, const double* __restrict__ uhat_b,
+__global__ void k_bd_local(int nc, int m, const int* __restrict__ cbf, const double* __restrict__ uhat_b, int full,
                            double* __restrict__ bdl) {
   long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (long)nc * 3 * m) return;
-  const long ci = t / m;
-  const int j = (int)(t % m);
+  if (t >= (long)nc * 3 * 2 * m) return;
+  const long ci = t / (2 * m);
+  const int cc = (int)(t / m % 2), j = (int)(t % m);
   const int b = cbf[ci];
-  bdl[t] = b >= 0 ? uhat_b[(long)b * m + j] : 0.0;
+  double v = 0.0;
+  if (b >= 0) v = full ? uhat_b[((long)b * 2 + cc) * m + j] : (cc == 1 ? uhat_b[(long)b * m + j] : 0.0);
+  bdl[t] = v;
+}
+
+// flux of the prescribed normal values out of each cell: sum_i sigma|F_i| c^n_i,0
+__global__ void k_bd_flux(int nc, int m, const double* __restrict__ bdiv, const double* __restrict__ bdl,
+                          double* __restrict__ cflux) {
+  long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  double s = 0.0;
+  for (int i = 0; i < 3; ++i) s += bdiv[3 * c + i] * bdl[((c * 3 + i) * 2) * m];
+  cflux[c] = s;
 }
 
 // gnu[c] += -(Lift z, Lift z_adj)_K for the forward state (f, lam) and the
@@ -490,6 +503,7 @@ __device__ inline double row_dot(const LevelViewT<TS>& L, int fi, int rr, const 
   double acc = 0.0;
   for (int s = 0; s < 2; ++s) {
     int K = L.fcell[2 * fi + s];
+    if (K < 0) continue;  // do-nothing facet: one cell
     int i = L.floc[2 * fi + s];
     const TS* row = L.S + ((long)K * L.nK + i * m2 + rr) * L.nK;
     for (int i2 = 0; i2 < 3; ++i2) {
@@ -522,7 +536,7 @@ __global__ void k_gather_cells(LevelView L, const double* __restrict__ vK, doubl
   double acc = 0.0;
   for (int s = 0; s < 2; ++s) {
     int K = L.fcell[2 * fi + s], i = L.floc[2 * fi + s];
-    acc += vK[(long)K * L.nK + i * m2 + rr];
+    if (K >= 0) acc += vK[(long)K * L.nK + i * m2 + rr];
   }
   y[t] = acc;
 }
@@ -890,18 +904,19 @@ __global__ void k_uzawa_rhs(int nint, int m, const double* __restrict__ g, const
   double v = g[t];
   if (t % (2 * m) == 0) {
     int fi = (int)(t / (2 * m));
-    v += fdiv[2 * fi] * p0[fcell[2 * fi]] + fdiv[2 * fi + 1] * p0[fcell[2 * fi + 1]];
+    v += fdiv[2 * fi] * p0[fcell[2 * fi]];
+    if (fcell[2 * fi + 1] >= 0) v += fdiv[2 * fi + 1] * p0[fcell[2 * fi + 1]];
   }
   b[t] = v;
 }
 
 __global__ void k_uzawa_update(int nc, int m, const int* __restrict__ cell_dofs, const double* __restrict__ cdiv,
                                const double* __restrict__ area, const double* __restrict__ lam,
-                               double eps_inv, double* p0, double* part) {
+                               double eps_inv, const double* __restrict__ cflux, double* p0, double* part) {
   __shared__ double sh[TPB];
   double s1 = 0.0, s2 = 0.0;
   for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += (long)gridDim.x * blockDim.x) {
-    double dv = 0.0;
+    double dv = cflux ? cflux[c] : 0.0;  // prescribed boundary flux
     for (int i = 0; i < 3; ++i) {
       int d = cell_dofs[3 * c + i];
       if (d >= 0) dv += cdiv[3 * c + i] * lam[(long)d * 2 * m];
@@ -953,9 +968,12 @@ void launch_facet_flux(hipStream_t st, const QuadTables& Q, const double* X, con
     hipLaunchKernelGGL(k_facet_flux, dim3(nblk(nint, 64)), dim3(64), 0, st, Q, X, cells, fcell, floc, nint, coef,
                        na, flux);
 }
-void launch_bd_local(hipStream_t st, int nc, int m, const int* cbf, const double* uhat_b, double* bdl) {
-  const long n = (long)nc * 3 * m;
-  if (n > 0) hipLaunchKernelGGL(k_bd_local, dim3(nblk(n)), dim3(TPB), 0, st, nc, m, cbf, uhat_b, bdl);
+void launch_bd_flux(hipStream_t st, int nc, int m, const double* bdiv, const double* bdl, double* cflux) {
+  if (nc > 0) hipLaunchKernelGGL(k_bd_flux, dim3(nblk(nc)), dim3(TPB), 0, st, nc, m, bdiv, bdl, cflux);
+}
+void launch_bd_local(hipStream_t st, int nc, int m, const int* cbf, const double* uhat_b, int full, double* bdl) {
+  const long n = (long)nc * 3 * 2 * m;
+  if (n > 0) hipLaunchKernelGGL(k_bd_local, dim3(nblk(n)), dim3(TPB), 0, st, nc, m, cbf, uhat_b, full, bdl);
 }
 void launch_postprocess(hipStream_t st, const ElemLevel& E, int c0, int nbatch, const double* f, const double* lam,
                         double* ws, double* ustar, int* status) {
@@ -1134,10 +1152,10 @@ void launch_uzawa_rhs(hipStream_t st, int nint, int m, const double* g, const do
   hipLaunchKernelGGL(k_uzawa_rhs, dim3(nblk(n)), dim3(TPB), 0, st, nint, m, g, fdiv, fcell, p0, b);
 }
 void launch_uzawa_update(hipStream_t st, int nc, int m, const int* cell_dofs, const double* cdiv,
-                         const double* area, const double* lam, double eps_inv, double* p0, double* part,
-                         int nblocks) {
+                         const double* area, const double* lam, double eps_inv, const double* cflux, double* p0,
+                         double* part, int nblocks) {
   hipLaunchKernelGGL(k_uzawa_update, dim3(nblocks), dim3(TPB), 0, st, nc, m, cell_dofs, cdiv, area, lam,
-                     eps_inv, p0, part);
+                     eps_inv, cflux, p0, part);
 }
 
 }  // namespace hdgmg

@@ -40,7 +40,7 @@ struct ElemLevel {
   int na;
   const int* cell_dofs;     // [nc][3] interior facet ids, -1 on the boundary
   int m;
-  const double* bdl;        // [nc][3][m] prescribed tangential boundary values, or null
+  const double* bdl;        // [nc][3][2][m] prescribed boundary values (normal, tangential), or null
   const double* S;          // [nc][nK][nK] condensed blocks (the loads' boundary lift)
   double* fac;              // kept local factors (element_fac_size per cell, element i
                             // of cell c at fac[i * nc + c]), or null
@@ -76,8 +76,13 @@ void launch_wind_rt0(hipStream_t st, const QuadTables& Q0, const double* X, cons
 // flux[F] = int_F w . n_F for every interior facet (from its first cell).
 void launch_facet_flux(hipStream_t st, const QuadTables& Q, const double* X, const int* cells, const int* fcell,
                        const int* floc, int nint, const double* coef, int na, double* flux);
-// bdl[c][i][j] = uhat_b[cbf[3c+i]][j] (0 where cbf < 0).
-void launch_bd_local(hipStream_t st, int nc, int m, const int* cbf, const double* uhat_b, double* bdl);
+// bdl[c][i][comp][j] = the prescribed value of local facet i of cell c
+// (0 where cbf < 0): from uhat_b[cbf][comp][j] (full) or, tangential only,
+// from uhat_b[cbf][j] with comp 0 (normal) zero.
+void launch_bd_local(hipStream_t st, int nc, int m, const int* cbf, const double* uhat_b, int full, double* bdl);
+// cflux[c] = sum_i bdiv[c][i] bdl[c][i][0][0]: the cell's outflow of the
+// prescribed normal values (|K| div of the boundary lift)
+void launch_bd_flux(hipStream_t st, int nc, int m, const double* bdiv, const double* bdl, double* cflux);
 // gnu[c] += -(Lift z, Lift z_adj)_K for cells c0 .. c0+nbatch (forward
 // source f and skeleton vector lam, adjoint source fa and skeleton vector lama).
 // u* (stPost) of every cell in [c0, c0 + nbatch) at the data points:
@@ -169,9 +174,9 @@ void launch_scalar_move(hipStream_t st, double* sc, int from, int to);
 // Uzawa helpers
 void launch_uzawa_rhs(hipStream_t st, int nint, int m, const double* g, const double* fdiv,
                       const int* fcell, const double* p0, double* b);
-void launch_uzawa_update(hipStream_t st, int nc, int m, const int* cell_dofs,
-                         const double* cdiv, const double* area, const double* lam,
-                         double eps_inv, double* p0, double* part, int nblocks);
+void launch_uzawa_update(hipStream_t st, int nc, int m, const int* cell_dofs, const double* cdiv,
+                         const double* area, const double* lam, double eps_inv, const double* cflux, double* p0,
+                         double* part, int nblocks);
 
 constexpr int RED_BLOCKS = 512;
 // Largest vertex-patch block the Gauss-Seidel kernel holds in LDS.

@@ -197,7 +197,7 @@ struct hdgmg_ctx {
   // tangential Dirichlet data on the finest boundary facets
   std::vector<int> bfacets;   // boundary facets in facet order
   int* cbf = nullptr;         // [n_cells][3] boundary facet number or -1
-  double* bdl = nullptr;      // [n_cells][3][k+1] local boundary values
+  double* bdl = nullptr;      // [n_cells][3][2][k+1] local boundary values (normal, tangential)
   double* btan = nullptr;     // [n_boundary_facets][2] tangents t_F (first use of constant data)
   double* bvals = nullptr;    // [n_boundary_facets][k+1] coefficients built from constant data
   // Alg. 3 (hdgmg_picard_newton): previous velocity and state
@@ -205,6 +205,10 @@ struct hdgmg_ctx {
   double* a3_state = nullptr;
   double* a3_f = nullptr;     // pseudo-time load f + dt_inv u_{n-1}
   bool has_bd = false;
+  bool has_outflow = false;   // do-nothing facets: launch-per-colour kernels on every level
+  double* bdiv = nullptr;     // [n_cells][3] sigma |F| on Dirichlet boundary facets, else 0
+  double* cflux = nullptr;    // [n_cells] flux of the prescribed normal boundary values
+  bool has_flux = false;
   // FGMRES basis: V [(restart+1)][N_skel], Z [restart][N_skel], scalars
   double *gm_V = nullptr, *gm_Z = nullptr, *gm_h = nullptr, *gm_y = nullptr, *gm_part = nullptr;
   // allocations of one hdgmg_assemble (released by the next one)
@@ -460,7 +464,8 @@ hdgmg_status upload_level(hdgmg_ctx* ctx, const Level& L, int m, DevLevel& D) {
   D.colour_ptr = L.colour_ptr;
   // streaming kernels pay off on large levels; small ones keep the one-launch
   // Gauss-Seidel phase
-  D.fast = L.max_patch_facets <= FAST_NF && (long)L.nint * 2 * m >= ctx->opts.stream_dofs && ctx->opts.smoother == 0;
+  D.fast = L.max_patch_facets <= FAST_NF && (long)L.nint * 2 * m >= ctx->opts.stream_dofs && ctx->opts.smoother == 0 &&
+           !ctx->has_outflow;
   D.full = ctx->opts.oseen != 0;
   D.sp_words = fast_cell_words(D.nK, D.full);
   if (D.fast) {
@@ -1297,7 +1302,7 @@ hdgmg_status upload_vals(hdgmg_ctx* ctx, const std::vector<double>& h, const voi
 // row of the patch inverse (host FP64 factorisation), structure-of-arrays.
 hdgmg_status build_coarse(hdgmg_ctx* ctx) {
   ctx->Lc = -1;
-  if (ctx->opts.coarse_dofs <= 0 || ctx->opts.smoother != 0) return HDGMG_OK;
+  if (ctx->opts.coarse_dofs <= 0 || ctx->opts.smoother != 0 || ctx->has_outflow) return HDGMG_OK;
   int Lc = -1, vec = 0, nsmax = 0;
   for (int l = 0; l < ctx->J && l < COARSE_MAX_LEVELS; ++l) {
     const Level& L = ctx->lv[l];
@@ -1457,7 +1462,7 @@ hdgmg_status build_record_levels(hdgmg_ctx* ctx) {
     // the launched lowest-order levels (32-bit fields beyond 16-bit facet
     // indices); stream_dofs = 0 keeps the streaming kernels on every level
     if (L.nint > REC_MAX_FACETS || 2 * L.max_patch_facets > 32 || (D.fast && ctx->opts.stream_dofs == 0) ||
-        ctx->opts.smoother != 0)
+        ctx->opts.smoother != 0 || ctx->has_outflow)
       continue;
     const bool wide = ctx->opts.rec_wide || L.nint > 65535 || 2 * L.nint > (int)REC_DOF_MASK;
     LevelRecords R;
@@ -1771,6 +1776,10 @@ hdgmg_status hdgmg_setup(const hdgmg_mesh* mesh, int k, double beta, const doubl
     return HDGMG_EINVAL;
   }
   if (mesh->dim == 3 && mesh->coords && mesh->cells) {
+    if (mesh->n_outflow != 0) {
+      g_setup_error = "do-nothing facets are provided on triangular meshes only";
+      return HDGMG_EINVAL;
+    }
     if (!(beta >= 0) || !(gamma > 0)) {
       g_setup_error = "need beta >= 0, gamma > 0";
       return HDGMG_EINVAL;
@@ -1872,6 +1881,13 @@ hdgmg_status hdgmg_setup(const hdgmg_mesh* mesh, int k, double beta, const doubl
   L0.nc = mesh->n_cells;
   L0.X.assign(mesh->coords, mesh->coords + 2 * (size_t)L0.nv);
   L0.cells.assign(mesh->cells, mesh->cells + 3 * (size_t)L0.nc);
+  if (mesh->n_outflow < 0 || (mesh->n_outflow > 0 && !mesh->outflow)) {
+    g_setup_error = "n_outflow < 0, or outflow pairs missing";
+    delete ctx;
+    return HDGMG_EINVAL;
+  }
+  for (int i = 0; i < mesh->n_outflow; ++i) L0.outflow_in.push_back({mesh->outflow[2 * i], mesh->outflow[2 * i + 1]});
+  ctx->has_outflow = mesh->n_outflow > 0;
   std::string e = build_level(L0);
   for (int l = 1; l < ctx->J && e.empty(); ++l) {
     refine(ctx->lv[l - 1], ctx->lv[l]);
@@ -1941,7 +1957,7 @@ hdgmg_status hdgmg_setup(const hdgmg_mesh* mesh, int k, double beta, const doubl
     for (int c = 0; c < LF.nc; ++c)
       for (int i = 0; i < 3; ++i) cbf[3 * c + i] = num[LF.cell_facets[3 * c + i]];
     if ((s = upload(ctx, &ctx->cbf, cbf))) return fail(s);
-    if ((s = dalloc(ctx, &ctx->bdl, (size_t)LF.nc * 3 * (k + 1)))) return fail(s);
+    if ((s = dalloc(ctx, &ctx->bdl, (size_t)LF.nc * 3 * 2 * (k + 1)))) return fail(s);
   }
   const long n = ctx->K.ndof;
   double** vecs[] = {&ctx->x, &ctx->r, &ctx->r_old, &ctx->z, &ctx->p, &ctx->q, &ctx->b, &ctx->gvec, &ctx->lam};
@@ -1960,16 +1976,20 @@ hdgmg_status hdgmg_setup(const hdgmg_mesh* mesh, int k, double beta, const doubl
     int f = LF.int_facet[i];
     for (int sd = 0; sd < 2; ++sd) {
       int c = LF.facet_cells[2 * f + sd], li = LF.facet_loc[2 * f + sd];
-      fdiv[2 * i + sd] = LF.sigma[3 * c + li] * LF.len[f];
+      fdiv[2 * i + sd] = c < 0 ? 0.0 : LF.sigma[3 * c + li] * LF.len[f];  // one side on a do-nothing facet
     }
   }
+  std::vector<double> bdiv(3 * (size_t)LF.nc);
   for (int c = 0; c < LF.nc; ++c)
     for (int i = 0; i < 3; ++i) {
       int f = LF.cell_facets[3 * c + i];
       cdiv[3 * c + i] = LF.int_id[f] >= 0 ? LF.sigma[3 * c + i] * LF.len[f] : 0.0;
+      bdiv[3 * c + i] = LF.int_id[f] < 0 ? LF.sigma[3 * c + i] * LF.len[f] : 0.0;
     }
   if ((s = upload(ctx, &ctx->fdiv, fdiv))) return fail(s);
   if ((s = upload(ctx, &ctx->cdiv, cdiv))) return fail(s);
+  if ((s = upload(ctx, &ctx->bdiv, bdiv))) return fail(s);
+  if ((s = dalloc(ctx, &ctx->cflux, (size_t)LF.nc))) return fail(s);
   if ((s = upload(ctx, &ctx->area, area))) return fail(s);
   // workspace: element batches and patch factorisations share it
   size_t need = 0;
@@ -2285,18 +2305,31 @@ hdgmg_status hdgmg_set_newton(hdgmg_ctx* ctx, const double* state_prev) {
   return HDGMG_OK;
 }
 
-hdgmg_status hdgmg_set_dirichlet(hdgmg_ctx* ctx, const double* uhat_b) {
+static hdgmg_status set_dirichlet(hdgmg_ctx* ctx, const double* uhat_b, bool full) {
   if (ctx && ctx->d3) {
     return HDGMG_ESTATE;
   }
   if (!ctx) return HDGMG_EINVAL;
   ctx->has_bd = false;
+  ctx->has_flux = false;
   if (!uhat_b) return HDGMG_OK;
-  launch_bd_local(ctx->st, ctx->K.nc, ctx->k + 1, ctx->cbf, uhat_b, ctx->bdl);
+  launch_bd_local(ctx->st, ctx->K.nc, ctx->k + 1, ctx->cbf, uhat_b, full ? 1 : 0, ctx->bdl);
+  if (full) launch_bd_flux(ctx->st, ctx->K.nc, ctx->k + 1, ctx->bdiv, ctx->bdl, ctx->cflux);
   HIPC(hipGetLastError());
   HIPC(hipStreamSynchronize(ctx->st));
   ctx->has_bd = true;
+  ctx->has_flux = full;
   return HDGMG_OK;
+}
+
+hdgmg_status hdgmg_set_dirichlet(hdgmg_ctx* ctx, const double* uhat_b) { return set_dirichlet(ctx, uhat_b, false); }
+
+hdgmg_status hdgmg_set_dirichlet_full(hdgmg_ctx* ctx, const double* uhat_b) {
+  if (ctx && !ctx->d3 && ctx->opts.oseen) {
+    ctx->err = "hdgmg_set_dirichlet_full: normal boundary data with opts.oseen are not provided";
+    return HDGMG_ESTATE;
+  }
+  return set_dirichlet(ctx, uhat_b, true);
 }
 
 hdgmg_status hdgmg_set_dirichlet_velocity(hdgmg_ctx* ctx, const double* g_b) {
@@ -2520,8 +2553,8 @@ hdgmg_status hdgmg_solve_x0(hdgmg_ctx* ctx, const double* f_qp, const double* x0
                                      : fcg(ctx, ctx_scratch(ctx), ctx->b, ctx->lam, &its, &rel);
     if (s < 0) return s;
     if (s == HDGMG_NOT_CONVERGED) result = s;
-    launch_uzawa_update(st, KL.nc, KL.m, KL.cell_dofs, ctx->cdiv, ctx->area, ctx->lam, ctx->gamma, ctx->p0,
-                        ctx->part, RED_BLOCKS);
+    launch_uzawa_update(st, KL.nc, KL.m, KL.cell_dofs, ctx->cdiv, ctx->area, ctx->lam, ctx->gamma,
+                        ctx->has_flux ? ctx->cflux : nullptr, ctx->p0, ctx->part, RED_BLOCKS);
     launch_finalize(st, ctx->part, RED_BLOCKS, 2, ctx->sc, SC_DP);
     double hs[SC_N];
     HIPC(hipMemcpyAsync(hs, ctx->sc, sizeof(hs), hipMemcpyDeviceToHost, st));

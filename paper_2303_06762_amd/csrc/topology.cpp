@@ -47,10 +47,30 @@ std::string build_level(Level& L) {
     r = s;
   }
   L.nf = (int)(L.edges.size() / 2);
+  L.outflow.assign(L.nf, 0);
+  for (const auto& pr : L.outflow_in) {
+    const int a = std::min(pr.first, pr.second), b = std::max(pr.first, pr.second);
+    // facets are sorted by their vertex pair: binary search
+    int lo = 0, hi = L.nf - 1, hit = -1;
+    while (lo <= hi) {
+      const int mid = (lo + hi) / 2;
+      const int ea = L.edges[2 * mid], eb = L.edges[2 * mid + 1];
+      if (ea == a && eb == b) {
+        hit = mid;
+        break;
+      }
+      if (ea < a || (ea == a && eb < b))
+        lo = mid + 1;
+      else
+        hi = mid - 1;
+    }
+    if (hit < 0 || L.facet_cells[2 * hit + 1] >= 0) return "an outflow pair is not a boundary facet";
+    L.outflow[hit] = 1;
+  }
   L.int_id.assign(L.nf, -1);
   L.int_facet.clear();
   for (int f = 0; f < L.nf; ++f)
-    if (L.facet_cells[2 * f + 1] >= 0) {
+    if (L.facet_cells[2 * f + 1] >= 0 || L.outflow[f]) {
       L.int_id[f] = (int)L.int_facet.size();
       L.int_facet.push_back(f);
     }
@@ -109,6 +129,13 @@ void refine(const Level& C, Level& F) {
     F.X[2 * (C.nv + f)] = 0.5 * (p0[0] + p1[0]);
     F.X[2 * (C.nv + f) + 1] = 0.5 * (p0[1] + p1[1]);
   }
+  // both halves of a do-nothing facet are do-nothing facets
+  F.outflow_in.clear();
+  for (int f = 0; f < C.nf; ++f)
+    if (!C.outflow.empty() && C.outflow[f]) {
+      F.outflow_in.push_back({C.edges[2 * f], C.nv + f});
+      F.outflow_in.push_back({C.edges[2 * f + 1], C.nv + f});
+    }
   F.cells.resize(3 * (size_t)F.nc);
   F.parent.resize(F.nc);
   for (int c = 0; c < C.nc; ++c) {
@@ -237,14 +264,16 @@ void build_averaging(const Level& C, const Level& F, Averaging& A) {
       w[E1] += 0.5;
       w[E2] += 0.5;
     } else {
+      // half of coarse facet E: the mean of the two sides' CR fields at the
+      // fine midpoint (one side on a do-nothing facet)
       int v = a, E = b - C.nv;
       int w_end = C.edges[2 * E] == v ? C.edges[2 * E + 1] : C.edges[2 * E];
       w[E] += 1.0;
-      for (int s = 0; s < 2; ++s) {
+      const int nside = C.facet_cells[2 * E + 1] >= 0 ? 2 : 1;
+      for (int s = 0; s < nside; ++s) {
         int T = C.facet_cells[2 * E + s];
-        if (T < 0) continue;  // cannot happen for interior fine facets
-        w[facet_opposite(T, w_end)] += 0.25;
-        w[facet_opposite(T, v)] -= 0.25;
+        w[facet_opposite(T, w_end)] += 0.5 / nside;
+        w[facet_opposite(T, v)] -= 0.5 / nside;
       }
       (void)other_cell;
     }

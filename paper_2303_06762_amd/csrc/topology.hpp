@@ -17,8 +17,12 @@ struct Level {
   std::vector<int> cell_facets;   // [nc][3], facet opposite local vertex i
   std::vector<int> facet_cells;   // [nf][2] adjacent cells (-1 if none)
   std::vector<int> facet_loc;     // [nf][2] local facet index in that cell
-  std::vector<int> int_id;        // [nf] interior number or -1
-  std::vector<int> int_facet;     // [nint] facet of each interior number
+  // do-nothing (outflow) facets: input vertex pairs (sorted), then a flag
+  // per facet; they carry unknowns and are numbered with the interior ones
+  std::vector<std::pair<int, int>> outflow_in;
+  std::vector<char> outflow;      // [nf]
+  std::vector<int> int_id;        // [nf] unknown-carrying (interior or do-nothing) number, or -1
+  std::vector<int> int_facet;     // [nint] facet of each such number
   std::vector<double> tang, norm; // [nf][2] facet frame
   std::vector<double> len;        // [nf]
   std::vector<double> area;       // [nc]
