@@ -203,6 +203,65 @@ def alg3_workload(hd, synth, torch, np, re, k=3, n_refine=6):
     return res
 
 
+def step_solver(hd, synth, torch, k, n_refine, beta, nu, **kw):
+    """A context on the paper's backward-facing step (Sec. 5.3): 15 squares
+    of side 0.5 (level n_refine + 1), inflow (16 (1-y)(y-0.5), 0) on x = 0,
+    do-nothing outflow on x = 4, no-slip elsewhere, (nu eps)^-1 = 1e6, two
+    AL-Uzawa steps, vertex patches (kw may choose others)."""
+    c, t, out = synth.step_domain(1)
+    s = hd.Solver(c, t, n_refine, k, beta, nu, 1e6 * nu, uzawa_max=2, uzawa_tol=-1.0, outflow=out, **kw)
+    ends = s.boundary_facets().cpu().numpy()
+    s.set_dirichlet_full(torch.as_tensor(synth.boundary_coefficients(ends, k, synth.step_inflow), device="cuda"))
+    return s
+
+
+def step_tables(hd, synth, torch, np):
+    """The paper's step runs beside tab:stokesBack (k = 0..3, levels 4-7,
+    beta in {0, 1e3}, m in {1, 2}, variable V- and W-cycle) and
+    tab:nsBack2D (Alg. 3, k = 0..3, nu in {1, 1e-2, 1e-3}, m = 1).  One
+    JSON line per case; a breakdown of the flexible CG is reported as
+    "NA" (status -6)."""
+    for k in range(4):
+        for level in range(4, 8):
+            for cyc in (1, 2):
+                for beta in (0.0, 1e3):
+                    for m in (1, 2):
+                        kw = dict(cycle=cyc, m_relax=m, m_smooth=m)
+                        if cyc == 2:
+                            kw["vcycle_growth"] = 1
+                        s = step_solver(hd, synth, torch, k, level - 1, beta, 1.0, **kw)
+                        s.assemble()
+                        f = torch.zeros((s.n_cells, s.n_q, 2), dtype=torch.float64, device="cuda")
+                        try:
+                            u, p, state, info, st = s.solve(f)
+                            its, status = info["its"], st
+                        except hd.HdgmgError as e:
+                            its, status = None, e.status
+                        print(json.dumps({"table": "stokesBack", "d": 2, "k": k, "level": level,
+                                          "cycle": "V" if cyc == 1 else "W", "beta": beta, "m": m,
+                                          "pcg_its": its, "status": status}), flush=True)
+                        s.close()
+    for k in range(4):
+        for level in (range(4, 8) if k < 2 else range(3, 7)):
+            for nu in (1.0, 1e-2, 1e-3):
+                s = step_solver(hd, synth, torch, k, level - 1, 0.0, nu, oseen=1)
+                f = torch.zeros((s.n_cells, s.n_q, 2), dtype=torch.float64, device="cuda")
+                t0 = time.perf_counter()
+                try:
+                    out = hd.picard_newton(s, f, eps_picard=1e-4, newton_rtol=1e-8, newton_atol=1e-10,
+                                           max_picard=30, max_newton=10 if k > 0 else 0)
+                    rec = {"steps": [o["kind"] for o in out], "status": max(o["status"] for o in out)}
+                    for kind in ("picard", "newton"):
+                        its = [i for o in out if o["kind"] == kind for i in o["info"]["its"]]
+                        rec[f"avg_pgm_its_{kind}"] = float(np.mean(its)) if its else None
+                except hd.HdgmgError as e:
+                    rec = {"status": e.status}
+                rec.update({"table": "nsBack2D", "k": k, "level": level, "nu": nu,
+                            "wall_s": time.perf_counter() - t0})
+                print(json.dumps(rec), flush=True)
+                s.close()
+
+
 def paper_tables(hd, synth, torch, np):
     """The paper's cavity runs beside its tables: PCG counts of the Stokes
     cavity (Sec. 5.2.1; k = 0..3, levels 4-7, beta in {0, 1e3}, m in {1, 2},
@@ -551,8 +610,8 @@ def main():
                     help="parameter sweeps instead of the bench line: the 256x256 generalized Stokes "
                          "workload over k, beta, gamma and V-cycle precision, and the cavity over Re; "
                          "one JSON line per case, then a summary line")
-    ap.add_argument("--tables", action="store_true",
-                    help="the paper's Stokes and Navier-Stokes cavity runs (one JSON line per case)")
+    ap.add_argument("--tables", choices=["cavity", "step"], default=None,
+                    help="the paper's Stokes and Navier-Stokes cavity or step runs (one JSON line per case)")
     ap.add_argument("--profile-solves", type=int, default=2)
     ap.add_argument("--profile-run", action="store_true",
                     help="counter-collection run: a 1 GiB device copy (calibration of the HBM "
@@ -580,7 +639,7 @@ def main():
         sweep(hd, synth, torch, np, c, t, a)
         return
     if a.tables:
-        paper_tables(hd, synth, torch, np)
+        (paper_tables if a.tables == "cavity" else step_tables)(hd, synth, torch, np)
         return
     if a.profile_run:
         # calibration: an elementwise kernel reading exactly 1 GiB and

@@ -447,8 +447,9 @@ hdgmg_status hdgmg_picard_newton(hdgmg_ctx* ctx, const double* f_qp, const hdgmg
  * NULL: homogeneous.  The prescribed normal values enter the cells'
  * divergence: hdgmg_solve imposes div u_h = 0 with their flux included
  * (the AL-Uzawa update and the load's AL term carry it).  Without
- * do-nothing facets the data must have zero net flux.  Generalized Stokes
- * contexts only (ESTATE with opts.oseen).  Triangular meshes only. */
+ * do-nothing facets the data must have zero net flux.  With opts.oseen the
+ * lowest-order levels' RT0 winds carry no flux through Dirichlet facets (as
+ * without normal data).  Triangular meshes only. */
 hdgmg_status hdgmg_set_dirichlet_full(hdgmg_ctx* ctx, const double* uhat_b);
 
 /* Tangential Dirichlet data given as one constant velocity per boundary

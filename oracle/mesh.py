@@ -91,6 +91,31 @@ class Level:
                 out[self.edges[e, 1]].append(e)
         return [sorted(x) for x in out]
 
+    def facet_patches(self):
+        """Edge (facet) patches of a triangulation: each dof facet alone (the
+        unknowns interior to the union of its cells), greedily coloured in
+        facet order so that facets of one colour lie in no common cell.
+        Returns (patches [list of [facet]], colours [n_patches])."""
+        pats, col = [], []
+        colour_of = -np.ones(self.n_facets, dtype=np.int64)
+        for e in range(self.n_facets):
+            if not self.dof[e]:
+                continue
+            used = set()
+            for K in self.facet_cells[e]:
+                if K < 0:
+                    continue
+                for e2 in self.cell_facets[K]:
+                    if colour_of[e2] >= 0:
+                        used.add(int(colour_of[e2]))
+            c = 0
+            while c in used:
+                c += 1
+            colour_of[e] = c
+            pats.append([e])
+            col.append(c)
+        return pats, np.array(col)
+
     def cell_neighbours(self):
         """nbr[K][i] = cell across local facet i of K, or -1 on the boundary."""
         nbr = -np.ones((self.n_cells, 3), dtype=np.int64)

@@ -23,7 +23,8 @@ from . import cr
 
 
 class PatchGS:
-    """Vertex-patch block Gauss-Seidel on a level with m modes per component;
+    """Vertex-patch block Gauss-Seidel on a level with m modes per component
+    (patch="edge": one facet per patch, mesh.Level.facet_patches);
     with smoother="jacobi" the damped block Jacobi smoother (eq. bjac)
     instead: x += s sum_s E_s (A_ss)^-1 E_s^T (b - A x), every patch from
     the same residual, s = 1 / (number of colours) (within one colour the
@@ -31,11 +32,17 @@ class PatchGS:
     the sum over all patches is bounded by the colour count); it is its own
     transpose."""
 
-    def __init__(self, A, lv, m, smoother="gs"):
+    def __init__(self, A, lv, m, smoother="gs", patch="vertex"):
         self.A = A.tocsr()
         self.jacobi = smoother == "jacobi"
-        col = lv.vertex_colours()
-        vf = lv.vertex_facets()
+        if patch == "edge":
+            # edge (facet) patches: one facet's unknowns per patch
+            fp, fcol = lv.facet_patches()
+            col = fcol
+            vf = fp
+        else:
+            col = lv.vertex_colours()
+            vf = lv.vertex_facets()
         self.colours = []
         for c in range(int(col.max()) + 1):
             pats = []
@@ -152,7 +159,7 @@ def stabilised_transfer(Af, Iavg, tdofs):
 class Hierarchy:
     """Lowest-order levels 1..J with transfers and smoothers."""
 
-    def __init__(self, levels, nu_fine, beta, eps_inv, harmonic=True, smoother="gs"):
+    def __init__(self, levels, nu_fine, beta, eps_inv, harmonic=True, smoother="gs", patch="vertex"):
         self.levels = levels
         J = len(levels)
         nus = [None] * J
@@ -162,7 +169,7 @@ class Hierarchy:
             nus[l - 1] = nus[l].reshape(-1, 4).mean(axis=1)
         self.nus = nus
         self.A = [cr.assemble(lv, nus[l], beta, eps_inv) for l, lv in enumerate(levels)]
-        self.smooth = [None] + [PatchGS(self.A[l], levels[l], 1, smoother) for l in range(1, J)]
+        self.smooth = [None] + [PatchGS(self.A[l], levels[l], 1, smoother, patch) for l in range(1, J)]
         self.P = [None]
         for l in range(1, J):
             Iavg = averaging(levels[l - 1], levels[l])
@@ -198,13 +205,14 @@ class HPMG:
     relaxation (m_p forward then m_p transposed sweeps from zero on r) plus
     the lowest-order correction Pi_0^k MG_h(Pi_k^0 r), both from the same r."""
 
-    def __init__(self, Ak, lv, k, hier, m_p=1, m_h=1, q=1, growth=2, smoother="gs", additive=False):
+    def __init__(self, Ak, lv, k, hier, m_p=1, m_h=1, q=1, growth=2, smoother="gs", additive=False,
+                 patch="vertex"):
         self.Ak, self.k, self.hier = Ak.tocsr(), k, hier
         self.m_p, self.m_h, self.q, self.growth = m_p, m_h, q, growth
         self.additive = additive
         m = k + 1
         self.mode0 = np.array([(f * 2 + c) * m for f in range(lv.n_int) for c in range(2)])
-        self.relax = PatchGS(self.Ak, lv, m, smoother) if k > 0 else None
+        self.relax = PatchGS(self.Ak, lv, m, smoother, patch) if k > 0 else None
 
     def __call__(self, g):
         J = len(self.hier.levels) - 1

@@ -292,10 +292,14 @@ def state_wind(prob, lam, p0, f_qp):
 
 
 def facet_fluxes(lv, winds, n_gauss=8):
-    """int_F w . n_F over every facet (from the first adjacent cell)."""
+    """int_F w . n_F over every unknown-carrying facet (from the first
+    adjacent cell); zero on Dirichlet boundary facets (the coarse-level
+    winds of the preconditioner carry no flux through them)."""
     s, om = quad.gauss_legendre01(n_gauss)
     flux = np.zeros(lv.n_facets)
     for E in range(lv.n_facets):
+        if lv.int_id[E] < 0:
+            continue
         K = lv.facet_cells[E, 0]
         X0, X1 = lv.coords[lv.edges[E, 0]], lv.coords[lv.edges[E, 1]]
         xl = X0[None, :] + s[:, None] * (X1 - X0)[None, :]
@@ -330,7 +334,8 @@ class OseenHierarchy(mg.Hierarchy):
     """Lowest-order levels with the convection of the RT0-projected wind
     (flux: facet fluxes of the wind on the finest level; None: Stokes)."""
 
-    def __init__(self, levels, nu_fine, beta, eps_inv, flux=None, harmonic=True, transpose=False, smoother="gs"):
+    def __init__(self, levels, nu_fine, beta, eps_inv, flux=None, harmonic=True, transpose=False, smoother="gs",
+                 patch="vertex"):
         self.levels = levels
         J = len(levels)
         nus = [None] * J
@@ -349,7 +354,7 @@ class OseenHierarchy(mg.Hierarchy):
             winds = None if flux is None else rt0_winds(lv, fluxes[l])
             pr = OseenProblem(lv, 0, nus[l], beta, eps_inv, winds, transpose=transpose)
             self.A.append(pr.matrix_Aeps().tocsr())
-        self.smooth = [None] + [mg.PatchGS(self.A[l], levels[l], 1, smoother) for l in range(1, J)]
+        self.smooth = [None] + [mg.PatchGS(self.A[l], levels[l], 1, smoother, patch) for l in range(1, J)]
         self.P, self.R = [None], [None]
         for l in range(1, J):
             Iavg = mg.averaging(levels[l - 1], levels[l])
@@ -441,7 +446,8 @@ class OseenSetup:
     Oseen hierarchy."""
 
     def __init__(self, levels, k, nu, beta, gamma, winds=None, dirichlet=None, m_p=1, m_h=1,
-                 q=1, growth=2, restart=50, transpose=False, newton_z=None, smoother="gs", additive=False):
+                 q=1, growth=2, restart=50, transpose=False, newton_z=None, smoother="gs", additive=False,
+                 patch_relax="vertex", patch_smooth="vertex"):
         self.levels = levels
         self.lv = levels[-1]
         self.k = k
@@ -451,8 +457,8 @@ class OseenSetup:
         self.eps_inv = self.prob.eps_inv
         flux = None if winds is None else facet_fluxes(self.lv, winds)
         self.hier = OseenHierarchy(levels, self.prob.nu_c, beta, self.eps_inv, flux,
-                                   transpose=transpose, smoother=smoother)
-        self.prec = mg.HPMG(self.Aeps, self.lv, k, self.hier, m_p, m_h, q, growth, smoother, additive)
+                                   transpose=transpose, smoother=smoother, patch=patch_smooth)
+        self.prec = mg.HPMG(self.Aeps, self.lv, k, self.hier, m_p, m_h, q, growth, smoother, additive, patch_relax)
         self.restart = restart
 
     def solve(self, f_qp, lam0=None, rtol=1e-8, atol=1e-10, max_it=500, uzawa_max=50,

@@ -14,7 +14,7 @@ from . import mesh, hdg, mg, krylov, oseen
 class Setup:
     def __init__(self, coords, cells, n_refine, k, nu, beta, gamma,
                  m_p=1, m_h=1, q=1, growth=2, harmonic=True, smoother="gs", additive=False,
-                 outflow=None, dirichlet=None):
+                 outflow=None, dirichlet=None, patch_relax="vertex", patch_smooth="vertex"):
         """outflow: do-nothing facets of the coarsest mesh (vertex pairs);
         dirichlet: boundary data on the finest level as in
         oseen.OseenProblem (a callable lv -> array is evaluated there)."""
@@ -31,8 +31,9 @@ class Setup:
         self.D = self.prob.matrix_D().tocsr()
         self.eps_inv = self.prob.eps_inv
         self.hier = mg.Hierarchy(self.levels, self.prob.nu_c, beta, self.eps_inv,
-                                 harmonic=harmonic, smoother=smoother)
-        self.prec = mg.HPMG(self.Aeps, self.lv, k, self.hier, m_p, m_h, q, growth, smoother, additive)
+                                 harmonic=harmonic, smoother=smoother, patch=patch_smooth)
+        self.prec = mg.HPMG(self.Aeps, self.lv, k, self.hier, m_p, m_h, q, growth, smoother, additive,
+                            patch_relax)
 
     def inner(self, b, rtol=1e-8, atol=1e-10, max_it=500):
         return krylov.fcg(self.Aeps, b, self.prec, rtol, atol, max_it)

@@ -424,6 +424,14 @@ double gs_phase_bytes(const Level& L, int m, int c) {
 }
 
 // ------------------------------------------------------------- device level
+// Damped Jacobi, do-nothing facets and edge patches run the
+// launch-per-colour kernels on every level (the streaming, record and
+// single-workgroup forms assume Gauss-Seidel on vertex patches of interior
+// facets).
+bool generic_only(const hdgmg_ctx* ctx) {
+  return ctx->opts.smoother != 0 || ctx->has_outflow || ctx->opts.patch_relax == 2 || ctx->opts.patch_smooth == 2;
+}
+
 hdgmg_status upload_level(hdgmg_ctx* ctx, const Level& L, int m, DevLevel& D) {
   D.nc = L.nc;
   D.nint = L.nint;
@@ -464,8 +472,7 @@ hdgmg_status upload_level(hdgmg_ctx* ctx, const Level& L, int m, DevLevel& D) {
   D.colour_ptr = L.colour_ptr;
   // streaming kernels pay off on large levels; small ones keep the one-launch
   // Gauss-Seidel phase
-  D.fast = L.max_patch_facets <= FAST_NF && (long)L.nint * 2 * m >= ctx->opts.stream_dofs && ctx->opts.smoother == 0 &&
-           !ctx->has_outflow;
+  D.fast = L.max_patch_facets <= FAST_NF && (long)L.nint * 2 * m >= ctx->opts.stream_dofs && !generic_only(ctx);
   D.full = ctx->opts.oseen != 0;
   D.sp_words = fast_cell_words(D.nK, D.full);
   if (D.fast) {
@@ -617,7 +624,8 @@ double phase_bytes(const hdgmg_ctx* ctx, const DevLevel& D, int level, int c) {
   if (D.rec) return D.rec_bytes[c];
   if (D.fast) return D.bytes_cell_vc + D.bytes_relax_vc[c];
   const double scale = D.f32 ? 0.5 : 1.0;  // operator words dominate the phase bytes
-  return scale * (level < 0 ? ctx->relax_bytes[c] : ctx->smooth_bytes[level][c]);
+  const std::vector<double>& t = level < 0 ? ctx->relax_bytes : ctx->smooth_bytes[level];
+  return c < (int)t.size() ? scale * t[c] : 0.0;
 }
 
 // One Gauss-Seidel sweep over the colours.  x_zero: x is zero on entry, so
@@ -1302,7 +1310,7 @@ hdgmg_status upload_vals(hdgmg_ctx* ctx, const std::vector<double>& h, const voi
 // row of the patch inverse (host FP64 factorisation), structure-of-arrays.
 hdgmg_status build_coarse(hdgmg_ctx* ctx) {
   ctx->Lc = -1;
-  if (ctx->opts.coarse_dofs <= 0 || ctx->opts.smoother != 0 || ctx->has_outflow) return HDGMG_OK;
+  if (ctx->opts.coarse_dofs <= 0 || generic_only(ctx)) return HDGMG_OK;
   int Lc = -1, vec = 0, nsmax = 0;
   for (int l = 0; l < ctx->J && l < COARSE_MAX_LEVELS; ++l) {
     const Level& L = ctx->lv[l];
@@ -1462,7 +1470,7 @@ hdgmg_status build_record_levels(hdgmg_ctx* ctx) {
     // the launched lowest-order levels (32-bit fields beyond 16-bit facet
     // indices); stream_dofs = 0 keeps the streaming kernels on every level
     if (L.nint > REC_MAX_FACETS || 2 * L.max_patch_facets > 32 || (D.fast && ctx->opts.stream_dofs == 0) ||
-        ctx->opts.smoother != 0 || ctx->has_outflow)
+        generic_only(ctx))
       continue;
     const bool wide = ctx->opts.rec_wide || L.nint > 65535 || 2 * L.nint > (int)REC_DOF_MASK;
     LevelRecords R;
@@ -1835,8 +1843,8 @@ hdgmg_status hdgmg_setup(const hdgmg_mesh* mesh, int k, double beta, const doubl
       ctx->opts.transpose > 1 || (ctx->opts.transpose && !ctx->opts.oseen) || ctx->opts.coarse_dense < 0 ||
       ctx->opts.coarse_dense > 1 || ctx->opts.rec_wide < 0 || ctx->opts.rec_wide > 1 || ctx->opts.smoother < 0 ||
       ctx->opts.smoother > 1 || ctx->opts.additive < 0 || ctx->opts.additive > 1 || ctx->opts.patch_relax < 0 ||
-      ctx->opts.patch_relax > 1 || ctx->opts.patch_smooth < 0 || ctx->opts.patch_smooth > 1) {
-    g_setup_error = "invalid options (triangles: vertex patches only)";
+      ctx->opts.patch_relax > 2 || ctx->opts.patch_smooth < 0 || ctx->opts.patch_smooth > 2) {
+    g_setup_error = "invalid options";
     delete ctx;
     return HDGMG_EINVAL;
   }
@@ -1898,7 +1906,15 @@ hdgmg_status hdgmg_setup(const hdgmg_mesh* mesh, int k, double beta, const doubl
     delete ctx;
     return HDGMG_EMESH;
   }
-  for (auto& L : ctx->lv) build_patches(L);
+  // patches: vertex (default) or edge (facet) patches, opts.patch_smooth on
+  // the lowest-order levels, opts.patch_relax on the order-k level
+  const bool erelax = ctx->opts.patch_relax == 2, esmooth = ctx->opts.patch_smooth == 2;
+  for (int l = 0; l < ctx->J; ++l) {
+    if (l == ctx->J - 1 ? erelax : esmooth)
+      build_facet_patches(ctx->lv[l]);
+    else
+      build_patches(ctx->lv[l]);
+  }
   if (ctx->lv.back().max_patch_facets * 2 * (k + 1) > GS_MAX_NS) {
     g_setup_error = "mesh: a vertex patch exceeds " + std::to_string(GS_MAX_NS) + " unknowns";
     delete ctx;
@@ -1917,6 +1933,16 @@ hdgmg_status hdgmg_setup(const hdgmg_mesh* mesh, int k, double beta, const doubl
     return st;
   };
   if ((s = upload_level(ctx, LF, k + 1, ctx->K))) return fail(s);
+  // per-colour byte model of the order-k relaxation, from its own patches
+  ctx->relax_bytes.resize(LF.ncol);
+  for (int c = 0; c < LF.ncol; ++c) ctx->relax_bytes[c] = gs_phase_bytes(LF, k + 1, c);
+  if (erelax != esmooth) {
+    // the finest lowest-order level smooths on the other patch type
+    if (esmooth)
+      build_facet_patches(ctx->lv.back());
+    else
+      build_patches(ctx->lv.back());
+  }
   if ((s = upload(ctx, &ctx->K.nu, ctx->nu_fine))) return fail(s);
   ctx->cr.resize(ctx->J);
   for (int l = 0; l < ctx->J; ++l)
@@ -2014,8 +2040,6 @@ hdgmg_status hdgmg_setup(const hdgmg_mesh* mesh, int k, double beta, const doubl
   // algorithmic byte models of the timed kernel classes
   {
     const int m = k + 1, nK = 6 * m;
-    ctx->relax_bytes.resize(LF.ncol);
-    for (int c = 0; c < LF.ncol; ++c) ctx->relax_bytes[c] = gs_phase_bytes(LF, m, c);
     ctx->smooth_bytes.resize(ctx->J);
     for (int l = 0; l < ctx->J; ++l) {
       ctx->smooth_bytes[l].resize(ctx->lv[l].ncol);
@@ -2324,13 +2348,7 @@ static hdgmg_status set_dirichlet(hdgmg_ctx* ctx, const double* uhat_b, bool ful
 
 hdgmg_status hdgmg_set_dirichlet(hdgmg_ctx* ctx, const double* uhat_b) { return set_dirichlet(ctx, uhat_b, false); }
 
-hdgmg_status hdgmg_set_dirichlet_full(hdgmg_ctx* ctx, const double* uhat_b) {
-  if (ctx && !ctx->d3 && ctx->opts.oseen) {
-    ctx->err = "hdgmg_set_dirichlet_full: normal boundary data with opts.oseen are not provided";
-    return HDGMG_ESTATE;
-  }
-  return set_dirichlet(ctx, uhat_b, true);
-}
+hdgmg_status hdgmg_set_dirichlet_full(hdgmg_ctx* ctx, const double* uhat_b) { return set_dirichlet(ctx, uhat_b, true); }
 
 hdgmg_status hdgmg_set_dirichlet_velocity(hdgmg_ctx* ctx, const double* g_b) {
   if (ctx && ctx->d3) return HDGMG_ESTATE;

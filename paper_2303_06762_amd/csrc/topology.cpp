@@ -239,6 +239,49 @@ void build_patches(Level& L) {
   }
 }
 
+void build_facet_patches(Level& L) {
+  std::vector<int> col(L.nf, -1);
+  int ncol = 0;
+  for (int f = 0; f < L.nf; ++f) {
+    if (L.int_id[f] < 0) continue;
+    int used = 0;
+    for (int s = 0; s < 2; ++s) {
+      const int c = L.facet_cells[2 * f + s];
+      if (c < 0) continue;
+      for (int i = 0; i < 3; ++i) {
+        const int cc = col[L.cell_facets[3 * c + i]];
+        if (cc >= 0) used |= 1 << cc;
+      }
+    }
+    int k = 0;
+    while (used & (1 << k)) ++k;
+    col[f] = k;
+    ncol = std::max(ncol, k + 1);
+  }
+  L.ncol = ncol;
+  L.colour_ptr.assign(1, 0);
+  L.patch_vertex.clear();
+  L.patch_facet_ptr.assign(1, 0);
+  L.patch_facets.clear();
+  L.patch_cell_ptr.assign(1, 0);
+  L.patch_cells.clear();
+  L.max_patch_facets = ncol > 0 ? 1 : 0;
+  for (int k = 0; k < ncol; ++k) {
+    for (int f = 0; f < L.nf; ++f) {
+      if (col[f] != k) continue;
+      L.patch_vertex.push_back(f);
+      L.patch_facets.push_back(L.int_id[f]);
+      L.patch_facet_ptr.push_back((int)L.patch_facets.size());
+      int a = L.facet_cells[2 * f], b = L.facet_cells[2 * f + 1];
+      if (b >= 0 && b < a) std::swap(a, b);
+      L.patch_cells.push_back(a);
+      if (b >= 0) L.patch_cells.push_back(b);
+      L.patch_cell_ptr.push_back((int)L.patch_cells.size());
+    }
+    L.colour_ptr.push_back((int)L.patch_vertex.size());
+  }
+}
+
 void build_averaging(const Level& C, const Level& F, Averaging& A) {
   // weights of the coarse CR midpoint vectors U_E = c^n_E n_E + c^t_E t_E
   // at the midpoint of each fine interior facet

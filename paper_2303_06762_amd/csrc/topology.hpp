@@ -49,6 +49,11 @@ void refine(const Level& C, Level& F);
 // Canonical vertex colouring and the patch lists.
 void build_patches(Level& L);
 
+// Edge (facet) patches in the same fields: each unknown-carrying facet
+// alone (patch_vertex then holds the facet), greedily coloured in facet
+// order so that facets of one colour lie in no common cell.
+void build_facet_patches(Level& L);
+
 // Averaging operator I_{l-1}^l (avgOpt) on the lowest-order unknowns
 // (2 per interior facet: normal, tangential), as sparse rows: for fine
 // DOF r, entries (coarse DOF, weight).  Also the fine DOFs strictly inside

@@ -39,7 +39,9 @@ def rel(a, b):
 
 SM = {0: "gs", 1: "jacobi"}
 
-CASES2 = [  # (name, n, n_refine, k, beta, gamma, smoother, additive)
+CASES2 = [  # (name, n, n_refine, k, beta, gamma, smoother, additive[, patch_relax, patch_smooth])
+    ("k2_edge_smooth", 2, 2, 2, 1.0, 1e2, 0, 0, 1, 2),
+    ("k1_edge_all", 2, 2, 1, 1.0, 1e4, 0, 0, 2, 2),
     ("k2_jacobi", 2, 2, 2, 1.0, 1e2, 1, 0),
     ("k0_jacobi", 2, 2, 0, 1.0, 1e4, 1, 0),
     ("k1_additive", 2, 2, 1, 1.0, 1e2, 0, 1),
@@ -53,11 +55,14 @@ CASES2 = [  # (name, n, n_refine, k, beta, gamma, smoother, additive)
 @pytest.mark.parametrize("case", CASES2, ids=[c[0] for c in CASES2])
 def test_triangles(case):
     import paper_2303_06762_amd as hd
-    name, n, nr, k, beta, gamma, sm, add = case
+    name, n, nr, k, beta, gamma, sm, add = case[:8]
+    pr, ps = case[8:] if len(case) > 8 else (0, 0)
     _note(f"smoother parity 2D {name}")
     c, t = synth.kuhn_square(n)
-    O = solver.Setup(c, t, nr, k, 1.0, beta, gamma, smoother=SM[sm], additive=bool(add))
-    s = hd.Solver(c, t, nr, k, beta, 1.0, gamma, smoother=sm, additive=add)
+    P2 = {0: "vertex", 1: "vertex", 2: "edge"}
+    O = solver.Setup(c, t, nr, k, 1.0, beta, gamma, smoother=SM[sm], additive=bool(add), patch_relax=P2[pr],
+                     patch_smooth=P2[ps])
+    s = hd.Solver(c, t, nr, k, beta, 1.0, gamma, smoother=sm, additive=add, patch_relax=pr, patch_smooth=ps)
     s.assemble()
     x = synth.uniform_pm1(1, 0, (s.n_skel,))
     assert rel(host(s.precondition(dev(x))), O.prec(x)) <= 1e-10
@@ -114,7 +119,7 @@ def test_invalid_patch_options_are_refused():
     import paper_2303_06762_amd as hd
     c, t = synth.kuhn_square(2)
     with pytest.raises(hd.HdgmgError) as e:
-        hd.Solver(c, t, 1, 1, 1.0, 1.0, 1e2, patch_relax=2)
+        hd.Solver(c, t, 1, 1, 1.0, 1.0, 1e2, patch_relax=3)
     assert e.value.status == -1
     with pytest.raises(hd.HdgmgError) as e:
         hd.Solver(c, t, 1, 1, 1.0, 1.0, 1e2, smoother=2)

@@ -3,7 +3,9 @@
 
 FP64 bars as for the square: cell blocks, load, apply and one MG_hp
 application within 1e-10 of the oracle's; inner and AL-Uzawa solves with
-counts within +-1 and iterates within 1e-9; the Poiseuille flow of the
+counts within +-1 and iterates within 1e-9 (with the edge-patch smoother,
+whose longer recurrences carry rounding further: 1e-8 for an inner solve,
+the solve tolerance, 1e-7 for the chained AL-Uzawa solves); the Poiseuille flow of the
 channel reproduced (k = 2, 3); on the step the outflow flux equals the
 inflow's 1/3 and every cell is divergence free to the Uzawa tolerance.
 """
@@ -67,21 +69,26 @@ def test_channel_poiseuille(k):
     s.close()
 
 
-CASES = [  # (name, n_refine, k, beta, gamma)
+CASES = [  # (name, n_refine, k, beta, gamma[, patch_relax, patch_smooth])
     ("k0", 2, 0, 1.0, 1e2),
     ("k1", 2, 1, 0.0, 1e3),
     ("k2", 1, 2, 1e3, 1e2),
     ("k2_J3", 2, 2, 0.0, 1e3),
+    # the paper's step setting: vertex-patch relaxation, edge-patch smoothing
+    ("k2_J3_edge_smooth", 2, 2, 0.0, 1e3, 1, 2),
 ]
 
 
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 def test_step_matches_oracle(case):
-    name, nr, k, beta, gamma = case
+    name, nr, k, beta, gamma = case[:5]
+    pr, ps = case[5:] if len(case) > 5 else (0, 0)
     _note(f"step parity {name}")
     c, t, out = synth.step_domain(1)
-    O = solver.Setup(c, t, nr, k, 1.0, beta, gamma, outflow=out, dirichlet=lambda lv: _inflow_lv(lv, k))
-    s = gpu(True, nr, k, beta=beta, gamma=gamma)
+    P2 = {0: "vertex", 1: "vertex", 2: "edge"}
+    O = solver.Setup(c, t, nr, k, 1.0, beta, gamma, outflow=out, dirichlet=lambda lv: _inflow_lv(lv, k),
+                     patch_relax=P2[pr], patch_smooth=P2[ps])
+    s = gpu(True, nr, k, beta=beta, gamma=gamma, patch_relax=pr, patch_smooth=ps)
     assert s.n_skel == O.Aeps.shape[0]
     lv = O.lv
     S = host(s.export(0))
@@ -96,7 +103,11 @@ def test_step_matches_oracle(case):
     xg, its, rr, st = s.inner_solve(dev(b))
     xo, its_o, _ = O.inner(b)
     assert st == 0 and abs(its - its_o) <= 1, (its, its_o)
-    assert rel(host(xg), xo) <= 1e-9
+    # the edge-patch smoother's longer recurrences carry the two sides'
+    # rounding further: its iterates agree to the solve tolerance
+    bar = 1e-8 if (pr, ps) != (0, 0) else 1e-9
+    assert np.linalg.norm(host(s.apply(xg)) - b) <= 1e-8 * np.linalg.norm(b)
+    assert rel(host(xg), xo) <= bar
     # full solve with the inflow: the load carries the lift of the
     # prescribed values, the Uzawa loop their flux
     u, p, state, info, st = s.solve(dev(f))
@@ -106,12 +117,14 @@ def test_step_matches_oracle(case):
     assert st == (1 if len(ref["its"]) == 50 else 0)
     assert len(info["its"]) == len(ref["its"])
     assert all(abs(a - b_) <= 1 for a, b_ in zip(info["its"], ref["its"])), (info["its"], ref["its"])
+    # (the full solve chains one inner solve per Uzawa step)
+    fbar = 1e-9 if (pr, ps) == (0, 0) else 1e-7
     lam = host(state)[:s.n_skel]
-    assert rel(lam, ref["lam"]) <= 1e-9
-    assert rel(host(state)[s.n_skel:], ref["p0"]) <= 1e-8
+    assert rel(lam, ref["lam"]) <= fbar
+    assert rel(host(state)[s.n_skel:], ref["p0"]) <= 10 * fbar
     uo, po, _, _ = O.prob.recover(ref["lam"], ref["p0"], f)
-    assert rel(host(u), uo) <= 1e-9
-    assert rel(host(p), po) <= 1e-8
+    assert rel(host(u), uo) <= fbar
+    assert rel(host(p), po) <= 10 * fbar
     # mass: every cell divergence free with the inflow flux, so the outflow
     # flux is the inflow's 1/3
     # (checked where the Uzawa loop converged)
@@ -147,4 +160,43 @@ def test_step_level5_properties():
     inner = X[..., 0] > 0.5
     q = np.sum((W * U[..., 0])[inner]) / 3.5
     assert abs(q - 1.0 / 3.0) <= 1e-6, q
+    s.close()
+
+
+def test_step_oseen_matches_oracle():
+    # an Oseen system on the step (the wind a discrete Stokes velocity of
+    # the step, the inflow data, do-nothing outflow): blocks, MG_hp and the
+    # AL-Uzawa + FGMRES solve as the oracle's
+    import paper_2303_06762_amd as hd
+    from oracle import hdg, mesh, oseen
+    k, nu, nr = 2, 0.05, 2
+    c, t, out = synth.step_domain(1)
+    levels = mesh.hierarchy(c, t, nr, out)
+    lv = levels[-1]
+    nq = (k + 2) ** 2
+    D = _inflow_lv(lv, k)
+    pr0 = oseen.OseenProblem(lv, k, 1.0, 0.0, 1e2, None, D)
+    f0 = np.zeros((lv.n_cells, nq, 2))
+    lam0, p00 = pr0.solve_direct(f0)
+    winds = oseen.state_wind(pr0, lam0, p00, f0)
+    wq = np.array([winds[K](pr0.elems[K].xq) for K in range(lv.n_cells)])
+    _note("step oseen k=2")
+    S = oseen.OseenSetup(levels, k, nu, 0.0, 1e2, winds, D)
+    s = hd.Solver(c, t, nr, k, 0.0, nu, 1e2, oseen=1, outflow=out)
+    ends = host(s.boundary_facets())
+    s.set_dirichlet_full(dev(synth.boundary_coefficients(ends, k, synth.step_inflow)))
+    s.set_wind(dev(wq))
+    s.assemble()
+    ref_b = np.array([e.S + S.eps_inv / e.area * np.outer(e.d, e.d) for e in S.prob.elems])
+    assert rel(host(s.export(0)), ref_b) <= 1e-10
+    r = synth.uniform_pm1(11, 0, (s.n_skel,))
+    assert rel(host(s.precondition(dev(r))), S.prec(r)) <= 1e-10
+    f = synth.source_uniform(7, 1, lv.n_cells, nq)[0]
+    u, p, state, info, st = s.solve(dev(f))
+    ref = S.solve(f)
+    assert st == 0
+    assert all(abs(a - b_) <= 1 for a, b_ in zip(info["its"], ref["its"])), (info["its"], ref["its"])
+    assert rel(host(state)[:s.n_skel], ref["lam"]) <= 1e-9
+    uo, _, _, _ = S.prob.recover(ref["lam"], ref["p0"], f)
+    assert rel(host(u), uo) <= 1e-9
     s.close()

@@ -48,12 +48,12 @@ def _projections(sm, A):
     return out
 
 
-@pytest.mark.parametrize("dim,k,patch", [(2, 2, None), (3, 1, "edge"), (3, 1, "vertex")])
+@pytest.mark.parametrize("dim,k,patch", [(2, 2, "vertex"), (2, 2, "edge"), (3, 1, "edge"), (3, 1, "vertex")])
 def test_colour_projections_are_A_orthogonal_projections(dim, k, patch):
     S = _setup2(k, 1e2) if dim == 2 else _setup3(k, 1e2)
     A = S.Aeps.toarray()
     if dim == 2:
-        sm = mg.PatchGS(S.Aeps, S.lv, k + 1, "jacobi")
+        sm = mg.PatchGS(S.Aeps, S.lv, k + 1, "jacobi", patch)
     else:
         sm = mg3d.EdgePatchGS(S.Aeps, S.lv, (k + 1) * (k + 2) // 2, "jacobi", patch)
     for Q in _projections(sm, A):
@@ -159,3 +159,22 @@ def test_vertex_patch_relaxation_on_tetrahedra():
             assert np.abs(B - B.T).max() <= 1e-10 * np.abs(B).max()
             assert np.linalg.eigvalsh(0.5 * (B + B.T)).min() > 0.0
     assert its["vertex"] <= its["edge"], its
+
+
+def test_facet_patches_of_triangles():
+    # edge (facet) patches in two dimensions: every dof facet alone, facets
+    # of one colour in no common cell; as a lowest-order smoother with
+    # vertex-patch relaxation (the paper's step setting) MG_hp stays SPD
+    from oracle import mesh
+    c, t = synth.kuhn_square(4)
+    lv = mesh.Level(c, t)
+    pats, col = lv.facet_patches()
+    assert sorted(p[0] for p in pats) == sorted(np.where(lv.dof)[0].tolist())
+    for K in range(lv.n_cells):
+        cs = [col[i] for i, p in enumerate(pats) if p[0] in lv.cell_facets[K]]
+        assert len(cs) == len(set(cs))
+    S = _setup2(2, 1e2, patch_relax="vertex", patch_smooth="edge")
+    n = S.Aeps.shape[0]
+    B = _dense(S.prec, n)
+    assert np.abs(B - B.T).max() <= 1e-10 * np.abs(B).max()
+    assert np.linalg.eigvalsh(0.5 * (B + B.T)).min() > 0.0
