@@ -101,6 +101,23 @@ def convection_matrix(e, wind):
             else:
                 trial[na + f * m:na + (f + 1) * m] = phi[l]
             C += (L * om[l] * wn[l]) * np.outer(test, trial)
+        if getattr(lv, "outflow", None) is not None and lv.outflow[E]:
+            # do-nothing facet: + <(w.n) u, vhat> (tangential: the facet
+            # unknown's test; normal: the cell's normal trace), so that the
+            # natural condition is (nu grad u - p I) n = 0 rather than the
+            # total-flux condition (with - (w.n) u) that the conservative
+            # volume form leaves on a one-sided facet
+            un = Pv @ nK
+            for l in range(len(s)):
+                tt = np.zeros(nz)
+                tt[na + f * m:na + (f + 1) * m] = phi[l]
+                tn = np.zeros(nz)
+                tn[:na] = un[l]
+                tr_t = np.zeros(nz)
+                tr_t[:na] = ut[l]
+                tr_n = np.zeros(nz)
+                tr_n[:na] = un[l]
+                C += (L * om[l] * wn[l]) * (np.outer(tt, tr_t) + np.outer(tn, tr_n))
     return C
 
 
@@ -153,6 +170,20 @@ def newton_matrix(e, wind, z_prev):
             trial = np.zeros(nz)
             trial[:na] = un[l]
             N += (L * om[l] * up) * np.outer(test, trial)
+        if getattr(lv, "outflow", None) is not None and lv.outflow[E]:
+            # derivative of the do-nothing facet term in its first argument:
+            # <(du.n) u_prev, v^>
+            a_prev = z_prev[:na]
+            for l in range(len(s)):
+                upt = ut[l] @ a_prev
+                upn = un[l] @ a_prev
+                tt = np.zeros(nz)
+                tt[na + f * m:na + (f + 1) * m] = phi[l]
+                tn = np.zeros(nz)
+                tn[:na] = un[l]
+                trial = np.zeros(nz)
+                trial[:na] = un[l]
+                N += (L * om[l]) * (upt * np.outer(tt, trial) + upn * np.outer(tn, trial))
     return N
 
 

@@ -233,6 +233,21 @@ __global__ void __launch_bounds__(WL) k_condense_wave(ElemLevel E, double* __res
             else
               H[(long)b * nz + na + i * m + tr] += tv * bphi[tr];
           }
+          const bool oflow = E.oflag && ((E.oflag[c] >> i) & 1);
+          if (oflow) {
+            __syncthreads();  // the upwind terms above touch the same entries
+            // do-nothing facet: + <(w.n_K) u, vhat> (tangential on the facet
+            // unknowns' rows, normal on the cell's normal trace), so that the
+            // natural condition is (nu grad u - p I) n = 0
+            for (int e = lane; e < (na + m) * na; e += WL) {
+              const int bt = e / na, tr = e % na;
+              const int b = bt < na ? bt : na + i * m + (bt - na);
+              const double tv = bt < na ? bu[6 * bt] * nk[0] + bu[6 * bt + 1] * nk[1] : bphi[bt - na];
+              const double uv = bt < na ? bu[6 * tr] * nk[0] + bu[6 * tr + 1] * nk[1]
+                                        : bu[6 * tr] * t[0] + bu[6 * tr + 1] * t[1];
+              H[(long)b * nz + tr] += cw * tv * uv;
+            }
+          }
           // (boundary facets: the increment's normal trace vanishes there and
           // u_prev.n_K is zero up to rounding, so the term is left out)
           if (newton && E.cell_dofs[3 * c + i] >= 0) {
@@ -257,6 +272,26 @@ __global__ void __launch_bounds__(WL) k_condense_wave(ElemLevel E, double* __res
               const int b = bt < na ? bt : na + i * m + (bt - na);
               const double tv = bt < na ? bu[6 * bt] * t[0] + bu[6 * bt + 1] * t[1] : -bphi[bt - na];
               nl[b] += cw * up * tv;
+            }
+            if (oflow) {
+              __syncthreads();
+              // the do-nothing term's derivative in its first argument,
+              // <(du.n_K) u_prev, vhat>, and its load (w.n_K) <u_prev, vhat>
+              // (the wind is u_prev: its tangential and normal traces)
+              double upt = 0.0;
+              for (int cc = 0; cc < na; ++cc) upt += wc[cc] * (bu[6 * cc] * t[0] + bu[6 * cc + 1] * t[1]);
+              const double cl = CT->ws[l] * g.len[i];
+              for (int e = lane; e < (na + m) * na; e += WL) {
+                const int bt = e / na, tr = e % na;
+                const int b = bt < na ? bt : na + i * m + (bt - na);
+                const double tv = bt < na ? wn * (bu[6 * bt] * nk[0] + bu[6 * bt + 1] * nk[1]) : upt * bphi[bt - na];
+                H[(long)b * nz + tr] += cl * tv * (bu[6 * tr] * nk[0] + bu[6 * tr + 1] * nk[1]);
+              }
+              for (int bt = lane; bt < na + m; bt += WL) {
+                const int b = bt < na ? bt : na + i * m + (bt - na);
+                const double tv = bt < na ? wn * (bu[6 * bt] * nk[0] + bu[6 * bt + 1] * nk[1]) : upt * bphi[bt - na];
+                nl[b] += cw * tv;
+              }
             }
           }
         }

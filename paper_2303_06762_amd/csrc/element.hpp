@@ -272,7 +272,8 @@ HDI int element_local(const QuadTables& Q, const CellGeom& g, double nu, double 
                       double eps_inv, int mode, const double* f, const double* lam,
                       double p0, WS w, double* out, const double* f2 = nullptr,
                       const double* lam2 = nullptr, const ConvTables* CT = nullptr,
-                      const double* wc = nullptr, const WS* fac = nullptr, bool transpose = false) {
+                      const double* wc = nullptr, const WS* fac = nullptr, bool transpose = false,
+                      int oflags = 0) {
   const Dims D = dims_of(Q.k);
   const int nP = D.nP, na = D.na, nz = D.nz, m = D.m, nK = D.nK, nN = D.nN, nkkt = D.nkkt;
   long o = 0;
@@ -430,6 +431,17 @@ HDI int element_local(const QuadTables& Q, const CellGeom& g, double nu, double 
             for (int a = 0; a < na; ++a) H[(long)b * nz + a] += tv * (u[2 * a] * t[0] + u[2 * a + 1] * t[1]);
           } else {
             for (int j = 0; j < m; ++j) H[(long)b * nz + na + i * m + j] += tv * phi[j];
+          }
+        }
+        if ((oflags >> i) & 1) {
+          // do-nothing facet: + <(w.n_K) u, vhat>, the tangential part on the
+          // facet unknowns' rows, the normal part on the cell's normal
+          // trace, so that the natural condition is (nu grad u - p I) n = 0
+          for (int a = 0; a < na; ++a) {
+            const double ut = u[2 * a] * t[0] + u[2 * a + 1] * t[1];
+            const double un = u[2 * a] * nK_[0] + u[2 * a + 1] * nK_[1];
+            for (int j = 0; j < m; ++j) H[(long)(na + i * m + j) * nz + a] += cw * phi[j] * ut;
+            for (int b = 0; b < na; ++b) H[(long)b * nz + a] += cw * (u[2 * b] * nK_[0] + u[2 * b + 1] * nK_[1]) * un;
           }
         }
       }

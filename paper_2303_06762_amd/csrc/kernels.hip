@@ -24,7 +24,7 @@ __global__ void k_condense(ElemLevel E, int c0, int nbatch, double* ws, double* 
   const WS fv{E.fac ? E.fac + c : nullptr, E.nc};
   int rc = element_local(E.Q, g, nuc, E.beta, E.eps_inv, EL_CONDENSE, nullptr, nullptr, 0.0, WS{ws + t, nbatch},
                          S + (long)c * nK * nK, nullptr, nullptr, E.CT, E.wcoef ? E.wcoef + (long)c * E.na : nullptr,
-                         E.fac ? &fv : nullptr, E.transpose != 0);
+                         E.fac ? &fv : nullptr, E.transpose != 0, E.oflag ? E.oflag[c] : 0);
   if (rc) atomicOr(status, 1);
 }
 
@@ -55,7 +55,7 @@ __global__ void k_load(ElemLevel E, int c0, int nbatch, const double* __restrict
   } else {
     int rc = element_local(E.Q, g, nuc, E.beta, 0.0, EL_LOAD, f + (long)c * E.Q.nq * 2, nullptr, 0.0,
                            WS{ws + t, nbatch}, out, nullptr, nullptr, E.CT,
-                           E.wcoef ? E.wcoef + (long)c * E.na : nullptr, nullptr, E.transpose != 0);
+                           E.wcoef ? E.wcoef + (long)c * E.na : nullptr, nullptr, E.transpose != 0, E.oflag ? E.oflag[c] : 0);
     if (rc) atomicOr(status, 1);
   }
   if (E.bdl) {
@@ -96,7 +96,7 @@ __global__ void k_recover(ElemLevel E, int c0, int nbatch, const double* __restr
   } else {
     int rc = element_local(E.Q, g, nuc, E.beta, 0.0, EL_RECOVER, f + (long)c * E.Q.nq * 2, lk, p0[c],
                            WS{ws + t, nbatch}, out, nullptr, nullptr, E.CT,
-                           E.wcoef ? E.wcoef + (long)c * E.na : nullptr, nullptr, E.transpose != 0);
+                           E.wcoef ? E.wcoef + (long)c * E.na : nullptr, nullptr, E.transpose != 0, E.oflag ? E.oflag[c] : 0);
     if (rc) atomicOr(status, 1);
   }
   for (int q = 0; q < E.Q.nq; ++q) {
@@ -128,7 +128,7 @@ __global__ void k_postprocess(ElemLevel E, int c0, int nbatch, const double* __r
   double nuc = E.nu_per_cell ? E.nu[c] : E.nu[0];
   int rc = element_local(E.Q, g, nuc, E.beta, 0.0, EL_POSTPROCESS, f + (long)c * E.Q.nq * 2, lk, 0.0,
                          WS{ws + t, nbatch}, ustar + (long)c * E.Q.nq * 2, nullptr, nullptr, E.CT,
-                         E.wcoef ? E.wcoef + (long)c * E.na : nullptr, nullptr, E.transpose != 0);
+                         E.wcoef ? E.wcoef + (long)c * E.na : nullptr, nullptr, E.transpose != 0, E.oflag ? E.oflag[c] : 0);
   if (rc) atomicOr(status, 1);
 }
 
@@ -254,7 +254,7 @@ __global__ void k_gradnu(ElemLevel E, int c0, int nbatch, const double* __restri
   double nuc = E.nu_per_cell ? E.nu[c] : E.nu[0];
   int rc = element_local(E.Q, g, nuc, E.beta, 0.0, EL_GRADNU, f + (long)c * E.Q.nq * 2, lk, 0.0,
                          WS{ws + t, nbatch}, out, fa + (long)c * E.Q.nq * 2, la, E.CT,
-                         E.wcoef ? E.wcoef + (long)c * E.na : nullptr);
+                         E.wcoef ? E.wcoef + (long)c * E.na : nullptr, nullptr, false, E.oflag ? E.oflag[c] : 0);
   if (rc) atomicOr(status, 1);
   gnu[c] += out[0];
 }

@@ -46,6 +46,8 @@ struct ElemLevel {
                             // of cell c at fac[i * nc + c]), or null
   int nc;
   int transpose;            // 1: cells of the transposed (adjoint) system (with a wind)
+  const int* oflag;         // [nc] bit i: local facet i is a do-nothing facet (the
+                            // convection form's outflow term), or null
   // Newton linearisation (order-k level, with a wind): the previous state's
   // skeleton vector [N_skel] and the per-cell Newton load written by the
   // condensation (element i of cell c at nw_load[i * nc + c], nz entries:

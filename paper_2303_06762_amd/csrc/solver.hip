@@ -71,6 +71,7 @@ struct DevLevel {
   long pinv_len = 0;
   std::vector<int> colour_ptr;
   double* nu = nullptr;  // per cell
+  int* oflag = nullptr;  // [nc] bit i: local facet i is a do-nothing facet (null without any)
   double *u = nullptr, *g = nullptr, *r = nullptr;  // multigrid vectors
   // record-based Gauss-Seidel (launched lowest-order levels): patch-row
   // records in the V-cycle's storage, batches per colour
@@ -451,6 +452,15 @@ hdgmg_status upload_level(hdgmg_ctx* ctx, const Level& L, int m, DevLevel& D) {
   }
   TRY(upload(ctx, &D.fcell, fc));
   TRY(upload(ctx, &D.floc, fl));
+  if (ctx->has_outflow) {
+    std::vector<int> of(L.nc, 0);
+    for (int c = 0; c < L.nc; ++c)
+      for (int i = 0; i < 3; ++i) {
+        const int f = L.cell_facets[3 * c + i];
+        if (L.int_id[f] >= 0 && L.facet_cells[2 * f + 1] < 0) of[c] |= 1 << i;
+      }
+    TRY(upload(ctx, &D.oflag, of));
+  }
   TRY(upload(ctx, &D.pf_ptr, L.patch_facet_ptr));
   TRY(upload(ctx, &D.pf, L.patch_facets));
   TRY(upload(ctx, &D.pc_ptr, L.patch_cell_ptr));
@@ -1586,6 +1596,7 @@ ElemLevel elem_level(const hdgmg_ctx* ctx, const DevLevel& D, bool order_k, bool
   E.fac = order_k ? ctx->fac : nullptr;
   E.nc = D.nc;
   E.transpose = E.CT && ctx->opts.transpose ? 1 : 0;
+  E.oflag = D.oflag;
   const bool nw = order_k && E.CT && ctx->has_newton;
   E.nw_lam = nw ? ctx->nw_lam : nullptr;
   E.nw_load = nw ? ctx->nw_load : nullptr;

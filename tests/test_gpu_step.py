@@ -200,3 +200,53 @@ def test_step_oseen_matches_oracle():
     uo, _, _, _ = S.prob.recover(ref["lam"], ref["p0"], f)
     assert rel(host(u), uo) <= 1e-9
     s.close()
+
+
+def test_channel_navier_stokes_poiseuille():
+    # Alg. 3 in the library on the channel: the Poiseuille flow solves the
+    # Navier-Stokes equations with p = 32 nu (4 - x), reproduced at k = 2
+    # (the do-nothing facets' convection term on both sides)
+    import paper_2303_06762_amd as hd
+    nu, k = 0.05, 2
+    _note("channel Navier-Stokes Poiseuille k=2")
+    c, t, out = synth.step_domain(1, step=False)
+    s = hd.Solver(c, t, 2, k, 0.0, nu, 1e2, oseen=1, outflow=out, uzawa_tol=1e-13, uzawa_max=64, rtol=1e-12,
+                  atol=0.0)
+    ends = host(s.boundary_facets())
+    s.set_dirichlet_full(dev(synth.boundary_coefficients(ends, k, synth.step_inflow)))
+    f = np.zeros((s.n_cells, s.n_q, 2))
+    res = hd.picard_newton(s, dev(f), eps_picard=1e-3, newton_rtol=1e-12, newton_atol=1e-13, max_newton=6)
+    assert res[-1]["kind"] == "newton" and all(o["status"] == 0 for o in res)
+    X = host(s.data_points())
+    u, p = host(res[-1]["u"]), host(res[-1]["p"])
+    assert np.abs(u[..., 0] - 16 * (1 - X[..., 1]) * (X[..., 1] - 0.5)).max() <= 1e-8
+    assert np.abs(u[..., 1]).max() <= 1e-8
+    assert np.abs(p - 32 * nu * (4.0 - X[..., 0])).max() <= 1e-6
+    s.close()
+
+
+def test_step_alg3_matches_oracle():
+    # Alg. 3 on the step (level 3, k = 2, nu = 1e-2): the step kinds, every
+    # step's velocity and inner counts as the oracle's Alg. 3
+    import paper_2303_06762_amd as hd
+    from oracle import mesh, oseen
+    k, nu, nr, gamma = 2, 1e-2, 2, 1e2
+    c, t, out = synth.step_domain(1)
+    levels = mesh.hierarchy(c, t, nr, out)
+    lv = levels[-1]
+    D = _inflow_lv(lv, k)
+    f = np.zeros((lv.n_cells, (k + 2) ** 2, 2))
+    _note("step alg3 k=2 nu=1e-2")
+    ref = oseen.picard_newton(levels, k, nu, 0.0, gamma, f, D, eps_picard=1e-3, max_picard=30, max_newton=6)
+    s = hd.Solver(c, t, nr, k, 0.0, nu, gamma, oseen=1, outflow=out)
+    ends = host(s.boundary_facets())
+    s.set_dirichlet_full(dev(synth.boundary_coefficients(ends, k, synth.step_inflow)))
+    res = hd.picard_newton(s, dev(f), eps_picard=1e-3, max_picard=30, max_newton=6)
+    assert [o["kind"] for o in res] == [r["kind"] for r in ref]
+    for o_, r_ in zip(res, ref):
+        assert o_["status"] == 0
+        assert rel(host(o_["u"]), r_["u"]) < 1e-7
+        for a, b_ in zip(o_["info"]["its"], r_["its"]):
+            assert abs(a - b_) <= 1, (o_["info"]["its"], r_["its"])
+    _note(f"  {len(res)} steps")
+    s.close()

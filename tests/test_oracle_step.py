@@ -87,3 +87,49 @@ def test_step_mass_conservation(k):
     r = S.solve(f, rtol=1e-12, atol=0.0, uzawa_tol=1e-13)
     assert np.abs(r["lam"] - lam).max() <= 1e-7 * np.abs(lam).max()
     assert np.abs(r["p0"] - p0).max() <= 1e-6 * np.abs(p0).max()
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_navier_stokes_poiseuille_in_the_channel(k):
+    # the Poiseuille flow also solves the Navier-Stokes equations ((u.grad)u
+    # = 0) with p = 32 nu (4 - x); the scheme reproduces it only if the
+    # convection form leaves the do-nothing condition (nu grad u - p I) n = 0
+    # on the outflow (the total-flux form would impose p = 32 nu (4 - x) -
+    # u_x^2 there, which no linear pressure meets)
+    nu = 0.05
+    c, t, out = synth.step_domain(1, step=False)
+    levels = mesh.hierarchy(c, t, 1, out)
+    lv = levels[-1]
+    D = np.zeros((lv.n_facets, 2, k + 1))
+    bnd = np.where(lv.int_id < 0)[0]
+    D[bnd] = synth.boundary_coefficients(lv.coords[lv.edges[bnd]], k, synth.step_inflow)
+    f = np.zeros((lv.n_cells, (k + 2) ** 2, 2))
+    steps = oseen.picard_newton(levels, k, nu, 0.0, 1e2, f, D, eps_picard=1e-3, direct=True, newton_rtol=1e-13,
+                                newton_atol=1e-14, max_newton=6)
+    last = steps[-1]
+    assert last["kind"] == "newton" and last["du"] <= 1e-10
+    u, p, _, _ = last["prob"].recover(last["lam"], last["p0"], f)
+    X = np.array([e.xq for e in last["prob"].elems])
+    assert np.abs(u[..., 0] - 16 * (1 - X[..., 1]) * (X[..., 1] - 0.5)).max() <= 1e-9
+    assert np.abs(u[..., 1]).max() <= 1e-9
+    assert np.abs(p - 32 * nu * (4.0 - X[..., 0])).max() <= 1e-8
+
+
+def test_navier_stokes_on_the_step_converges():
+    # Alg. 3 with direct linear solves on the step (level 3, k = 2) at
+    # nu = 1e-2 and 1e-3: Picard contracts and Newton converges
+    # quadratically (the outflow condition keeps the energy of the
+    # linearisations bounded)
+    k = 2
+    c, t, out = synth.step_domain(1)
+    levels = mesh.hierarchy(c, t, 2, out)
+    lv = levels[-1]
+    D = np.zeros((lv.n_facets, 2, k + 1))
+    bnd = np.where(lv.int_id < 0)[0]
+    D[bnd] = synth.boundary_coefficients(lv.coords[lv.edges[bnd]], k, synth.step_inflow)
+    f = np.zeros((lv.n_cells, (k + 2) ** 2, 2))
+    for nu in (1e-2, 1e-3):
+        steps = oseen.picard_newton(levels, k, nu, 0.0, 1e6 * nu, f, D, eps_picard=1e-4, direct=True,
+                                    max_picard=30, max_newton=10)
+        dn = [s["du"] for s in steps if s["kind"] == "newton"]
+        assert dn and dn[-1] <= 1e-8, (nu, dn)
