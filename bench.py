@@ -428,6 +428,16 @@ def sweep(hd, synth, torch, np, c, t, a):
     print(json.dumps({"sweep_cases": len(rows)}), flush=True)
 
 
+# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE runs of `bench.py --profile-run` (the same kernel and
+# workload), each scaled by what the counter reads for a copy kernel of
+# known size (FETCH_SIZE counts 0.500 of the bytes read, WRITE_SIZE 1.000 of
+# those written on this part); the summary, with its commands, is in
+# COUNTER_SOURCE.  Retake them whenever the kernel changes.
+COUNTER_TRAFFIC = {("order-k edge-patch Gauss-Seidel, one colour (k_patch_gs3)", 3): 11.096e9 + 0.027e9}
+COUNTER_SOURCE = "profiles/k_patch_gs3_fp64_k3_32cube.md"
+
+
 def progress(msg):
     """Progress on stderr (the JSON line alone goes to stdout)."""
     print(f"bench: {msg}", file=sys.stderr, flush=True)
@@ -704,7 +714,9 @@ def main():
                                   "FP64 operator"),
                   "vcycle": vcycle3(m32), "kernel_classes": classes3(m32["tm"])},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "frac": achieved / PEAK_HBM_GBS,
+                     "traffic": COUNTER_TRAFFIC.get((KCLASS3[by_time], a.k)),
+                     "traffic_source": COUNTER_SOURCE if (KCLASS3[by_time], a.k) in COUNTER_TRAFFIC else None,
                      "kernel": KCLASS3[by_time], "launches": n_l, "avg_us": 1e3 * ms / n_l,
                      "algorithmic_bytes_per_launch": by / n_l,
                      "bytes_model": "per colour phase: for each edge patch its inverse and, for each patch "
