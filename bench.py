@@ -623,6 +623,8 @@ def main():
     ap.add_argument("--tables", choices=["cavity", "step"], default=None,
                     help="the paper's Stokes and Navier-Stokes cavity or step runs (one JSON line per case)")
     ap.add_argument("--profile-solves", type=int, default=2)
+    ap.add_argument("--profile-dim", type=int, default=3, choices=[2, 3],
+                    help="--profile-run on the tetrahedral cube (3) or the 256x256 triangle workload (2)")
     ap.add_argument("--profile-run", action="store_true",
                     help="counter-collection run: a 1 GiB device copy (calibration of the HBM "
                          "counters) then two FP64 inner solves of the cube workload; prints a summary only")
@@ -659,15 +661,26 @@ def main():
         torch.add(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
-        c3, t3 = synth.kuhn_cube(4)
-        s = hd.Solver(c3, t3, 3, a.k, 1.0, 1.0, 1e3, atol=0.0, m_relax=2, m_smooth=2)
+        if a.profile_dim == 2:
+            # the triangle workload of the 2D line: 256x256, k = 2, gamma = 1e2
+            s = hd.Solver(c, t, a.n_refine, 2, 1.0, 1.0, 1e2, atol=0.0)
+        else:
+            c3, t3 = synth.kuhn_cube(4)
+            s = hd.Solver(c3, t3, 3, a.k, 1.0, 1.0, 1e3, atol=0.0, m_relax=2, m_smooth=2)
         s.assemble()
         g = torch.ones(s.n_skel, dtype=torch.float64, device="cuda")
         x = torch.empty_like(g)
         for _ in range(a.profile_solves):
             _, its, rel, st = s.inner_solve(g, x)
         torch.cuda.synchronize()
-        print(json.dumps({"profile_run": True, "n_skel": s.n_skel, "iterations": its}))
+        out = {"profile_run": True, "n_skel": s.n_skel, "iterations": its}
+        if a.profile_dim == 2:
+            # per level: lowest-order unknowns and nonzeros of the transfer
+            # into it (the counter summaries price the launches with these)
+            out["levels"] = [{"level": l, "n_lo": s.query(9, l),
+                              "transfer_nnz": s.query(14, l) if l else 0}
+                             for l in range(s.query(3))]
+        print(json.dumps(out))
         return
 
     # mixed storage: FP32 cell blocks (AL term apart, FP64) and lowest-order

@@ -519,7 +519,10 @@ hdgmg_status hdgmg_recover(hdgmg_ctx* ctx, const double* f_qp,
  *    plus vectors), 13 its compulsory bytes (every stored operator read
  *    once per use in packed symmetric form -- cell blocks n(n+1)/2 words,
  *    patch inverses n_s(n_s+1)/2, the coarsest inverse n_0(n_0+1)/2 -- in
- *    the storage precision, plus the vectors); both after hdgmg_assemble.
+ *    the storage precision, plus the vectors); both after hdgmg_assemble,
+ * 14 nonzeros of the lowest-order transfer from level `level` - 1 into
+ *    `level` (its transpose, the restriction, has the same count;
+ *    1 <= level < J, after hdgmg_assemble; triangles only).
  * level counts from 0 (coarsest) and is ignored by 0..7 and 10..13. */
 hdgmg_status hdgmg_query(const hdgmg_ctx* ctx, int what, int level, int64_t* value);
 

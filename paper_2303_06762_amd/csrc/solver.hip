@@ -2768,6 +2768,10 @@ hdgmg_status hdgmg_query(const hdgmg_ctx* ctx, int what, int level, int64_t* val
     case 11: *value = 2; return HDGMG_OK;
     case 12: *value = (int64_t)ctx->vcycle_bytes; return HDGMG_OK;
     case 13: *value = (int64_t)ctx->vcycle_compulsory; return HDGMG_OK;
+    case 14:
+      if (level < 1 || level >= ctx->J || !ctx->assembled) return HDGMG_EINVAL;
+      *value = ctx->tr[level].nnz;
+      return HDGMG_OK;
     default: return HDGMG_EINVAL;
   }
 }
