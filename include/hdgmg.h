@@ -108,11 +108,12 @@ typedef struct {
                               kernel (0: every level launch by launch)     */
   int stream_dofs;         /* levels with at least this many unknowns (and
                               vertex patches of at most 6 facets) use the
-                              streaming cell-apply / patch-relax kernels;
-                              lowest-order levels with at most 65535
-                              interior facets smooth with the patch-row
-                              record kernel instead, unless stream_dofs
-                              is 0 (streaming on every level)             */
+                              streaming kernels (see fused_phase); other
+                              launched lowest-order levels smooth with the
+                              patch-row record kernel, and so do streamed
+                              ones without the fused phase unless
+                              stream_dofs is 0 (streaming on every
+                              level)                                      */
   int vcycle_precision;    /* storage of every operator the preconditioner
                               reads: 0 FP64, 1 FP32, 2 FP32 with the
                               order-k level's streaming cell blocks (k <= 2,
@@ -179,6 +180,19 @@ typedef struct {
                               only: EINVAL on triangles)                   */
   int patch_smooth;        /* patches of the lowest-order smoothing, the
                               same codes                                   */
+  int fused_phase;         /* 1 (default): on every streamed level of a
+                              triangle mesh with symmetric blocks (the
+                              order-k level for k <= 2 and the lowest-order
+                              levels; vcycle_precision 0 or 1; vertex
+                              patches of at most 7 cells) a Gauss-Seidel
+                              colour phase is one launch that forms each
+                              patch's residual from its own cells, read
+                              from a per-colour, patch-ordered copy of the
+                              blocks; such lowest-order levels use it in
+                              place of the record kernel.  0: the
+                              cell-apply / patch-relaxation pair (records
+                              on the lowest-order levels).  Same iterates
+                              up to rounding; ignored on tetrahedra       */
 } hdgmg_opts;
 
 /* Defaults: m_p = m_h = 1, V-cycle, growth 2, rtol 1e-8, atol 1e-10,

@@ -37,7 +37,8 @@ class Opts(ctypes.Structure):
                 ("stream_dofs", ctypes.c_int), ("vcycle_precision", ctypes.c_int),
                 ("oseen", ctypes.c_int), ("restart", ctypes.c_int), ("transpose", ctypes.c_int),
                 ("coarse_dense", ctypes.c_int), ("rec_wide", ctypes.c_int), ("smoother", ctypes.c_int),
-                ("additive", ctypes.c_int), ("patch_relax", ctypes.c_int), ("patch_smooth", ctypes.c_int)]
+                ("additive", ctypes.c_int), ("patch_relax", ctypes.c_int), ("patch_smooth", ctypes.c_int),
+                ("fused_phase", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):

@@ -22,8 +22,21 @@
 //        with e(a, b) = a NS - a (a - 1) / 2 + b - a; a thread per (row,
 //        patch), 16 consecutive patches per row, so that a wavefront reads
 //        four 16-patch runs per step
+//   Sc   (fused colour phase) per colour, the blocks of each patch's cells
+//        in patch order, NCP slots per patch (zero padding slots): a slot
+//        holds its cell's block with the local facets reordered so that the
+//        facet opposite the patch vertex comes last, and of its packed upper
+//        triangle only the rows of the two patch facets (the last facet's
+//        diagonal block is never needed), fast_cell_words_patch words
+//   meta (fused colour phase) per patch of one colour, field-major
+//        ([field][np]): for each cell slot the interior ids of its three
+//        reordered facets (-1 on the boundary and in padding slots), and for
+//        each patch facet slot the two (cell slot, place among the cell's
+//        two patch facets) pairs holding it, one byte each (slot * 4 + place)
 // A Gauss-Seidel colour phase is a cell apply (y = S x for every cell) then
-// k_patch_relax (x_s += A_ss^-1 (b - y)_s for the colour's patches).
+// k_patch_relax (x_s += A_ss^-1 (b - y)_s for the colour's patches), or one
+// fused kernel (k_patch_gs_fused) that forms the patch residual from the
+// patch's own cells.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -251,6 +264,175 @@ __global__ void __launch_bounds__(64) k_patch_relax_wave(int np, const int* __re
   if (f >= 0) x[(long)f * M2 + c] += d;
 }
 
+// One Gauss-Seidel colour phase in one kernel, symmetric operators: a
+// wavefront per patch (per PPW consecutive patches).  Within a colour the
+// cells around a patch vertex belong to no other patch of the colour, the
+// patch facets to no other patch, and the cells' remaining facets to no
+// patch of the colour at all, so the residual rows of a patch come from its
+// own cells and from x values no other wavefront of the launch changes:
+//   r_s = b_s - sum over the patch cells K of (S_K x_K) on the patch rows,
+//   x_s += A_ss^-1 r_s.
+// The colour's cell blocks are stored patch by patch (Sc, see the layout
+// notes at the top), so a wavefront's blocks and triangles are two
+// contiguous runs, loaded with the metadata in the first round; the x and b
+// gathers wait on the metadata.  Every load is issued before the first LDS
+// store; the triangles go to LDS once the residual no longer needs the
+// blocks, and the update writes x_s from the copy gathered into LDS.
+// 16-byte words as a native vector (plain loads and stores, kept in
+// registers)
+typedef unsigned int U4 __attribute__((ext_vector_type(4)));
+template <int M2, int NCP, typename TS>
+struct FusedShape {
+  static constexpr int NS = FAST_NF * M2, NK = 3 * M2, PPW = WaveShape<M2>::PPW;
+  static constexpr int PW = fast_patch_words_sym(NS);
+  static constexpr int CR = fast_cell_words_patch(M2, (int)sizeof(TS));  // one slot
+  static constexpr int T16 = PPW * PW * (int)sizeof(TS) / 16;  // the wavefront's triangles
+  static constexpr int C16 = PPW * NCP * CR * (int)sizeof(TS) / 16;  // ... and cell blocks
+  static constexpr int NCELL = PPW * NCP;
+  static constexpr int NX = NCELL * NK;  // the cells' x values
+  static constexpr int NLT = (T16 + 63) / 64, NLC = (C16 + 63) / 64, NLX = (NX + 63) / 64;
+};
+// (LDS holds about 16 wavefronts per CU; four per SIMD leave 128 registers,
+// so that the triangles stay in registers while the residual is formed)
+template <int M2, int NCP, typename TS>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4)))
+k_patch_gs_fused(int np, const int* __restrict__ pf, const int* __restrict__ meta, const TS* __restrict__ Pp,
+                 const TS* __restrict__ Sc, const double* __restrict__ b, double* __restrict__ x) {
+  using F = FusedShape<M2, NCP, TS>;
+  constexpr int NS = F::NS, NK = F::NK, PPW = F::PPW, PW = F::PW, CR = F::CR;
+  constexpr int T16 = F::T16, C16 = F::C16, NX = F::NX;
+  __shared__ U4 Bs[T16 > C16 ? T16 : C16];  // the cell blocks, then the triangles
+  __shared__ double xs[NX];
+  __shared__ double rs[PPW * NS];
+  const int lane = threadIdx.x;
+  const int lp = lane / NS, i = lane % NS;  // patch of the wavefront, row
+  // workgroups go round-robin to the eight XCDs (each with its own L2):
+  // give each XCD a contiguous run of the colour's patches, whose cells,
+  // facets and x and b rows are neighbours (the last partial round keeps
+  // its order)
+  const int nb = gridDim.x, full = nb / 8 * 8;
+  const int g = (int)blockIdx.x < full ? ((int)blockIdx.x % 8) * (full / 8) + (int)blockIdx.x / 8 : (int)blockIdx.x;
+  const int p0 = g * PPW;
+  const int p = p0 + lp;
+  const bool on = lp < PPW && p < np;
+  // metadata first, every load unconditional (indices clamped into the
+  // colour; what a lane of a padding patch reads is never used): the x
+  // items' facets, the patch rows' facet and sides
+  int xf[F::NLX];
+#pragma unroll
+  for (int q = 0; q < F::NLX; ++q) {
+    const int t = min(lane + 64 * q, NX - 1), j = t / NK, lf = (t % NK) / M2;
+    xf[q] = meta[((j % NCP) * 3 + lf) * np + min(p0 + j / NCP, np - 1)];
+  }
+  const int pc = min(p, np - 1);
+  const int fr = pf[(i / M2) * np + pc];
+  const int ps = meta[(3 * NCP + i / M2) * np + pc];
+  const int f = on ? fr : -1;
+  const int c = i % M2;
+  // then the triangles and the cell blocks (a lane past the end of the
+  // colour re-reads its last word), then the x and b gathers
+  const long lastT = (long)np * PW * (long)sizeof(TS) / 16 - 1;
+  const long remT = lastT - (long)p0 * PW * (long)sizeof(TS) / 16;
+  const U4* srcT = (const U4*)(Pp + (long)p0 * PW);
+  U4 w[F::NLT];
+#pragma unroll
+  for (int q = 0; q < F::NLT; ++q) w[q] = srcT[min((long)min(lane + 64 * q, T16 - 1), remT)];
+  const long lastC = (long)np * NCP * CR * (long)sizeof(TS) / 16 - 1;
+  const long remC = lastC - (long)p0 * NCP * CR * (long)sizeof(TS) / 16;
+  const U4* srcC = (const U4*)(Sc + (long)p0 * NCP * CR);
+  U4 cw[F::NLC];
+#pragma unroll
+  for (int q = 0; q < F::NLC; ++q) cw[q] = srcC[min((long)min(lane + 64 * q, C16 - 1), remC)];
+  const double bv = b[(long)max(f, 0) * M2 + c];
+  double xv[F::NLX];
+#pragma unroll
+  for (int q = 0; q < F::NLX; ++q) {
+    const int t = min(lane + 64 * q, NX - 1);
+    const double v = x[(long)max(xf[q], 0) * M2 + t % M2];
+    xv[q] = xf[q] >= 0 ? v : 0.0;  // boundary facets carry no unknowns
+  }
+  // stores without branches: a lane past the end loaded the last word and
+  // writes it again
+#pragma unroll
+  for (int q = 0; q < F::NLC; ++q) Bs[min(lane + 64 * q, C16 - 1)] = cw[q];
+#pragma unroll
+  for (int q = 0; q < F::NLX; ++q) xs[min(lane + 64 * q, NX - 1)] = xv[q];
+  // the row's sides and b are used only after the barrier; an empty
+  // statement that takes both in registers keeps their loads with the others
+  asm volatile("" ::"v"(bv), "v"(ps));
+  __syncthreads();
+  double xrow;
+  // residual rows: lane (patch, row i = facet slot * M2 + c).  Every lane
+  // computes one without branches (so that the loads above stay ahead of
+  // the stores); lanes past the wavefront's patches and padding rows keep
+  // their slots and rows in range and discard the result.  A side's code
+  // is slot * 4 + its place (0 or 1) among the cell's two patch facets;
+  // row a < 2 M2 of a slot holds entries (a, b >= a) at
+  // e(a, b) = a NK - a (a - 1) / 2 + b - a, and (b < a, a) sits in row b.
+  {
+    const int lpc = min(lp, PPW - 1);
+    double y = 0.0;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int code = (ps >> (8 * s)) & 0xff;
+      const int slot = lpc * NCP + min(code >> 2, NCP - 1), row = min(code & 3, 1) * M2 + c;
+      const TS* S = (const TS*)Bs + slot * CR;
+      const double* xk = xs + slot * NK;
+      const int ro = row * NK - row * (row - 1) / 2 - row;
+#pragma unroll
+      for (int bb = 0; bb < NK; ++bb) {
+        const int e = bb >= row ? ro + bb : bb * NK - bb * (bb - 1) / 2 - bb + row;
+        y += (double)S[e] * xk[bb];
+      }
+    }
+    const double r = f >= 0 ? bv - y : 0.0;
+    if (lp < PPW) rs[lane] = r;
+    // x on the row (as gathered into the first side's cell)
+    const int code = ps & 0xff;
+    xrow = xs[(lpc * NCP + min(code >> 2, NCP - 1)) * NK + min(code & 3, 1) * M2 + c];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < F::NLT; ++q) Bs[min(lane + 64 * q, T16 - 1)] = w[q];
+  __syncthreads();
+  if (!on) return;
+  const TS* A = (const TS*)Bs + lp * PW;
+  const double* rr = rs + lp * NS;
+  const int rowi = i * NS - i * (i - 1) / 2 - i;
+  double d = 0.0;
+#pragma unroll
+  for (int j = 0; j < NS; ++j) {
+    const int colj = j * NS - j * (j - 1) / 2 - j;
+    const int e = j < i ? colj + i : rowi + j;
+    d += (double)A[e] * rr[j];
+  }
+  if (f >= 0) x[(long)f * M2 + c] = xrow + d;
+}
+
+// Full row-major FP64 cell blocks -> the patch-ordered slots of one colour:
+// slot t holds cell K = code >> 2 with its local facets reordered as (the
+// two others in increasing order, far = code & 3), the rows of the first
+// two reordered facets of the packed upper triangle; code < 0 (padding):
+// zeros.
+template <typename TS>
+__global__ void k_pack_cells_patch(int nslot, int m2, int cr, const int* __restrict__ code,
+                                   const double* __restrict__ S, TS* __restrict__ Sc) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nslot) return;
+  const int nK = 3 * m2, cd = code[t];
+  TS* out = Sc + (long)t * cr;
+  int e = 0;
+  if (cd >= 0) {
+    const int K = cd >> 2, far = cd & 3;
+    const int perm[3] = {far == 0 ? 1 : 0, far == 2 ? 1 : 2, far};
+    const double* B = S + (long)K * nK * nK;
+    for (int a = 0; a < 2 * m2; ++a)
+      for (int c = a; c < nK; ++c, ++e)
+        out[e] = (TS)B[(perm[a / m2] * m2 + a % m2) * nK + perm[c / m2] * m2 + c % m2];
+  }
+  for (; e < cr; ++e) out[e] = (TS)0;
+}
+
 // Full row-major cell blocks -> packed SoA in groups of G (G = 2 for the
 // FP64 copy; the FP32 copy is regrouped by k_regroup_f32).
 template <typename TS>
@@ -451,9 +633,43 @@ void patch_relax_t(hipStream_t st, int m2, int np, const int* pf, const TS* Pp, 
   }
 }
 
+template <typename TS>
+void patch_gs_fused_t(hipStream_t st, int m2, int ncp, int np, const int* pf, const int* meta, const TS* Pp,
+                      const TS* Sc, const double* b, double* x, const KernelEvents* ev) {
+#define CASE(M, N)                                                                                            \
+  if (m2 == M && ncp == N) {                                                                                 \
+    LAUNCH_EV((k_patch_gs_fused<M, N, TS>), dim3((np + WaveShape<M>::PPW - 1) / WaveShape<M>::PPW), dim3(64), \
+              np, pf, meta, Pp, Sc, b, x);                                                                   \
+    return;                                                                                                  \
+  }
+  CASE(2, 6) CASE(2, 7) CASE(4, 6) CASE(4, 7) CASE(6, 6) CASE(6, 7)
+#undef CASE
+}
+
 #undef LAUNCH_EV
 
 }  // namespace
+
+bool fast_fused_supported(int m2, int ncp) { return (m2 == 2 || m2 == 4 || m2 == 6) && (ncp == 6 || ncp == 7); }
+
+template <typename TS>
+void launch_patch_gs_fused(hipStream_t st, int m2, int ncp, int np, const int* pf, const int* meta, const TS* Pp,
+                           const TS* Sc, const double* b, double* x, const KernelEvents* ev) {
+  if (np > 0) patch_gs_fused_t<TS>(st, m2, ncp, np, pf, meta, Pp, Sc, b, x, ev);
+}
+template void launch_patch_gs_fused<double>(hipStream_t, int, int, int, const int*, const int*, const double*,
+                                            const double*, const double*, double*, const KernelEvents*);
+template void launch_patch_gs_fused<float>(hipStream_t, int, int, int, const int*, const int*, const float*,
+                                           const float*, const double*, double*, const KernelEvents*);
+
+template <typename TS>
+void launch_pack_cells_patch(hipStream_t st, int nslot, int m2, const int* code, const double* S, TS* Sc) {
+  if (nslot > 0)
+    hipLaunchKernelGGL(k_pack_cells_patch<TS>, dim3(nblk(nslot)), dim3(256), 0, st, nslot, m2,
+                       fast_cell_words_patch(m2, (int)sizeof(TS)), code, S, Sc);
+}
+template void launch_pack_cells_patch<double>(hipStream_t, int, int, const int*, const double*, double*);
+template void launch_pack_cells_patch<float>(hipStream_t, int, int, const int*, const double*, float*);
 
 template <typename TS>
 void launch_cell_apply(hipStream_t st, int m2, int nc, const TS* Sp, const int* cdof, const double* x,

@@ -22,6 +22,14 @@ inline long fast_cell_words(int nK, bool full = false) {
 }
 inline long fast_cell_words16(int nK) { return ((long)nK * (nK + 1) / 2 + 7) / 8 * 8; }
 
+// Words of one slot of the fused colour phase's cell storage: the rows of
+// two of the three facets (2 m2 rows of the reordered 3 m2 x 3 m2 block)
+// of the packed upper triangle, rounded up to whole 16-byte groups (word:
+// bytes per word).
+__host__ __device__ constexpr int fast_cell_words_patch(int m2, int word) {
+  return ((2 * m2 * 3 * m2 - 2 * m2 * (2 * m2 - 1) / 2) * word + 15) / 16 * 16 / word;
+}
+
 // Patch-inverse storage of the zero-padded NS = FAST_NF*m2 square inverses:
 // symmetric operators (full = false) the upper triangle, patch after patch,
 // NS(NS+1)/2 words rounded up to a multiple of 8 (16-byte aligned in every
@@ -56,6 +64,20 @@ template <typename TS>
 void launch_patch_relax(hipStream_t st, int m2, int np, const int* pf, const TS* Pp, const double* b,
                         const double* yF, double* x, bool full = true, const float* sc = nullptr,
                         const KernelEvents* ev = nullptr);
+// One Gauss-Seidel colour phase of symmetric operators in one launch
+// (x_s += A_ss^-1 (b - A x)_s for the np patches of the colour), from the
+// patches' upper-triangle inverses Pp, the colour's patch-ordered cell
+// slots Sc and its metadata (see fast.hip); m2 in {2, 4, 6} and ncp in {6, 7}
+// slots per patch (fast_fused_supported).
+bool fast_fused_supported(int m2, int ncp);
+template <typename TS>
+void launch_patch_gs_fused(hipStream_t st, int m2, int ncp, int np, const int* pf, const int* meta, const TS* Pp,
+                           const TS* Sc, const double* b, double* x, const KernelEvents* ev = nullptr);
+// Full row-major FP64 blocks S [nc][3 m2][3 m2] -> one colour's slots:
+// code[t] = cell * 4 + local index of the facet opposite the patch vertex,
+// or -1 for a padding slot.
+template <typename TS>
+void launch_pack_cells_patch(hipStream_t st, int nslot, int m2, const int* code, const double* S, TS* Sc);
 void launch_pack_cells(hipStream_t st, int nc, int nK, const double* S, double* Sp, bool full = false);
 // FP32 copy of packed blocks (pair groups -> quad groups).
 void launch_regroup_cells_f32(hipStream_t st, int nc, int nK, const double* Sp, float* Sp32);

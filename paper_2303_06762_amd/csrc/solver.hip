@@ -94,6 +94,14 @@ struct DevLevel {
   std::vector<int> npc;   // patches per colour
   std::vector<int*> pfc;  // per colour [FAST_NF][npc] facets
   std::vector<double*> Ppc;  // per colour packed SoA patch inverses
+  // fused colour phase (order-k level, symmetric packed blocks)
+  bool fused = false;
+  int fused_ncp = 0;             // cell slots per patch (6 or 7)
+  std::vector<int*> fmeta;       // per colour [3 ncp + FAST_NF][npc]
+  std::vector<int*> fcode;       // per colour [npc][ncp] cell * 4 + far facet, or -1
+  std::vector<double*> Scc;      // per colour patch-ordered cell slots, FP64
+  std::vector<float*> Scc32;     // ... or FP32 (the V-cycle's storage)
+  std::vector<double> bytes_fused_vc;
   bool pfull = true;         // patch inverses stored in full (else upper triangles)
   double bytes_cell = 0.0, bytes_sum = 0.0;
   std::vector<double> bytes_relax;
@@ -537,6 +545,116 @@ hdgmg_status upload_level(hdgmg_ctx* ctx, const Level& L, int m, DevLevel& D) {
   return HDGMG_OK;
 }
 
+// Metadata, byte model and patch-ordered cell storage of the fused colour
+// phase on the order-k level, when its streaming layout is symmetric and
+// packed, the V-cycle stores FP64 or FP32, and every patch has at most 7
+// cells (else the level keeps the cell-apply / patch-relaxation pair).
+hdgmg_status setup_fused(hdgmg_ctx* ctx, const Level& L, DevLevel& D) {
+  if (!D.fast || D.full || D.pfull || !fast_cell_packed(D.nK, false) || ctx->opts.vcycle_precision > 1)
+    return HDGMG_OK;
+  int maxc = 0;
+  for (int p = 0; p < D.npatch; ++p) maxc = std::max(maxc, L.patch_cell_ptr[p + 1] - L.patch_cell_ptr[p]);
+  const int m2 = 2 * D.m, ncp = maxc <= 6 ? 6 : 7;
+  if (maxc > 7 || !fast_fused_supported(m2, ncp)) return HDGMG_OK;
+  const bool f32 = vc_f32(ctx);
+  const double ws = f32 ? 4.0 : 8.0;
+  const int cr = fast_cell_words_patch(m2, (int)ws);
+  const long pw = fast_patch_words(m2, false);
+  const int nfield = 3 * ncp + FAST_NF;
+  std::vector<std::vector<int>> metas, codes;
+  std::vector<double> bytes;
+  for (int cc = 0; cc < L.ncol; ++cc) {
+    const int p0 = L.colour_ptr[cc], np = L.colour_ptr[cc + 1] - p0;
+    std::vector<int> meta((size_t)nfield * std::max(np, 1), -1), code((size_t)ncp * std::max(np, 1), -1);
+    double nfac = 0, nfar = 0;
+    for (int p = 0; p < np; ++p) {
+      const int gp = p0 + p, v = L.patch_vertex[gp];
+      const int c0 = L.patch_cell_ptr[gp], nk = L.patch_cell_ptr[gp + 1] - c0;
+      const int a0 = L.patch_facet_ptr[gp], na = L.patch_facet_ptr[gp + 1] - a0;
+      auto in_patch = [&](int fi) {
+        return fi >= 0 && std::binary_search(L.patch_facets.begin() + a0, L.patch_facets.begin() + a0 + na, fi);
+      };
+      std::vector<int> far_ids;
+      int perm[7][3];
+      for (int j = 0; j < nk; ++j) {
+        const int K = L.patch_cells[c0 + j];
+        int far = -1;
+        for (int lv = 0; lv < 3; ++lv)
+          if (L.cells[3 * K + lv] == v) far = lv;  // the facet opposite the patch vertex
+        if (far < 0) return HDGMG_OK;
+        perm[j][0] = far == 0 ? 1 : 0;
+        perm[j][1] = far == 2 ? 1 : 2;
+        perm[j][2] = far;
+        code[(size_t)p * ncp + j] = K * 4 + far;
+        for (int lf = 0; lf < 3; ++lf)
+          meta[(size_t)(j * 3 + lf) * np + p] = L.int_id[L.cell_facets[3 * K + perm[j][lf]]];
+        const int ff = L.int_id[L.cell_facets[3 * K + far]];
+        if (ff >= 0) far_ids.push_back(ff);
+        // the two patch facets of the cell are its other two facets
+        for (int lf = 0; lf < 2; ++lf) {
+          const int fi = L.int_id[L.cell_facets[3 * K + perm[j][lf]]];
+          if (fi >= 0 && !in_patch(fi)) return HDGMG_OK;
+        }
+        if (in_patch(ff)) return HDGMG_OK;
+      }
+      for (int a = 0; a < na; ++a) {
+        const int fi = L.patch_facets[a0 + a];
+        int cd = 0, found = 0;
+        for (int j = 0; j < nk; ++j)
+          for (int lf = 0; lf < 2; ++lf)
+            if (L.int_id[L.cell_facets[3 * L.patch_cells[c0 + j] + perm[j][lf]]] == fi && found < 2)
+              cd |= (j * 4 + lf) << (8 * found++);
+        if (found != 2) return HDGMG_OK;  // a patch facet outside the patch cells: keep the pair
+        meta[(size_t)(3 * ncp + a) * np + p] = cd;
+      }
+      std::sort(far_ids.begin(), far_ids.end());
+      nfar += (double)(std::unique(far_ids.begin(), far_ids.end()) - far_ids.begin());
+      nfac += na;
+    }
+    metas.push_back(std::move(meta));
+    codes.push_back(std::move(code));
+    // the triangles, the cell slots as stored, metadata and facet lists,
+    // b and x once per patch facet, x once per far facet, the update of x
+    bytes.push_back((double)np * pw * ws + (double)np * ncp * cr * ws + (double)np * (nfield + FAST_NF) * 4.0 +
+                    (3.0 * nfac + nfar) * m2 * 8.0);
+  }
+  for (int cc = 0; cc < L.ncol; ++cc) {
+    int *dm, *dc;
+    TRY(upload(ctx, &dm, metas[cc]));
+    TRY(upload(ctx, &dc, codes[cc]));
+    D.fmeta.push_back(dm);
+    D.fcode.push_back(dc);
+    const size_t n = codes[cc].size() * cr;
+    if (f32) {
+      float* q;
+      TRY(dalloc(ctx, &q, n));
+      D.Scc32.push_back(q);
+    } else {
+      double* q;
+      TRY(dalloc(ctx, &q, n));
+      D.Scc.push_back(q);
+    }
+  }
+  D.bytes_fused_vc = bytes;
+  D.fused_ncp = ncp;
+  D.fused = true;
+  return HDGMG_OK;
+}
+
+// The patch-ordered cell slots of a fused level from its assembled blocks.
+hdgmg_status pack_fused(hdgmg_ctx* ctx, const DevLevel& D) {
+  if (!D.fused) return HDGMG_OK;
+  for (size_t c = 0; c < D.fcode.size(); ++c) {
+    const int nslot = std::max(D.npc[c], 1) * D.fused_ncp;
+    if (!D.Scc32.empty())
+      launch_pack_cells_patch<float>(ctx->st, nslot, 2 * D.m, D.fcode[c], D.S, D.Scc32[c]);
+    else
+      launch_pack_cells_patch<double>(ctx->st, nslot, 2 * D.m, D.fcode[c], D.S, D.Scc[c]);
+  }
+  HIPC(hipGetLastError());
+  return HDGMG_OK;
+}
+
 hdgmg_status check_status(hdgmg_ctx* ctx, const char* what) {
   int h = 0;
   HIPC(hipMemcpyAsync(&h, ctx->status, sizeof(int), hipMemcpyDeviceToHost, ctx->st));
@@ -631,6 +749,7 @@ hdgmg_status upload_f32(hdgmg_ctx* ctx, float** p, const std::vector<T>& h) {
 // Algorithmic bytes of Gauss-Seidel colour phase c of a level (level < 0:
 // the order-k level) in the storage the V-cycle reads.
 double phase_bytes(const hdgmg_ctx* ctx, const DevLevel& D, int level, int c) {
+  if (D.fused) return D.bytes_fused_vc[c];
   if (D.rec) return D.rec_bytes[c];
   if (D.fast) return D.bytes_cell_vc + D.bytes_relax_vc[c];
   const double scale = D.f32 ? 0.5 : 1.0;  // operator words dominate the phase bytes
@@ -670,13 +789,25 @@ void sweep(hdgmg_ctx* ctx, DevLevel& D, double* x, const double* b, bool forward
   const int nc = (int)D.colour_ptr.size() - 1;
   for (int i = 0; i < nc; ++i) {
     int c = forward ? i : nc - 1 - i;
-    if (D.rec) {
+    if (D.fused && !(x_zero && i == 0)) {
+      // the colour phase in one launch
+      const int fcls = level < 0 ? 0 : 2;
+      const KtDispatch kf = kd_begin(ctx, fcls);
+      if (D.f32)
+        launch_patch_gs_fused<float>(ctx->st, 2 * D.m, D.fused_ncp, D.npc[c], D.pfc[c], D.fmeta[c], D.Pp32[c],
+                                     D.Scc32[c], b, x, kf.ptr());
+      else
+        launch_patch_gs_fused<double>(ctx->st, 2 * D.m, D.fused_ncp, D.npc[c], D.pfc[c], D.fmeta[c], D.Ppc[c],
+                                      D.Scc[c], b, x, kf.ptr());
+      kd_end(ctx, fcls, kf, D.bytes_fused_vc[c]);
+    } else if (D.rec) {
       int t = kt_begin(ctx, 2);
       launch_gs_records(ctx->st, D.rk, D.rv, D.ra, D.rnit, D.rnsm, D.rcb[c], D.rcb[c + 1] - D.rcb[c], x, b,
                         D.f32 ? 1 : 0, D.rwide ? 1 : 0);
       kt_end(ctx, 2, t, phase_bytes(ctx, D, level, c));
     } else if (D.fast) {
       // colour phase = cell apply (all cells) + patch relaxation (colour c)
+      // (the first phase from a zero iterate of a fused level: relaxation only)
       const bool skip = x_zero && i == 0;
       if (!skip) {
         const int ccls = level < 0 ? 1 : 2;
@@ -1479,7 +1610,7 @@ hdgmg_status build_record_levels(hdgmg_ctx* ctx) {
     // records replace the streaming pair (cell apply + patch relaxation) on
     // the launched lowest-order levels (32-bit fields beyond 16-bit facet
     // indices); stream_dofs = 0 keeps the streaming kernels on every level
-    if (L.nint > REC_MAX_FACETS || 2 * L.max_patch_facets > 32 || (D.fast && ctx->opts.stream_dofs == 0) ||
+    if (L.nint > REC_MAX_FACETS || 2 * L.max_patch_facets > 32 || (D.fast && ctx->opts.stream_dofs == 0) || D.fused ||
         generic_only(ctx))
       continue;
     const bool wide = ctx->opts.rec_wide || L.nint > 65535 || 2 * L.nint > (int)REC_DOF_MASK;
@@ -1646,6 +1777,7 @@ hdgmg_status assemble_levels(hdgmg_ctx* ctx) {
   TRY(patch_inverses(ctx, ctx->K));
   TRY(pack_fast(ctx, ctx->K));
   TRY(make_f32(ctx, ctx->K, true));
+  TRY(pack_fused(ctx, ctx->K));
   ctx->hostB.assign(ctx->J, {});
   std::vector<std::vector<double>> nu;
   level_viscosities(ctx->lv, ctx->nu_fine, nu);
@@ -1669,6 +1801,7 @@ hdgmg_status assemble_levels(hdgmg_ctx* ctx) {
     TRY(patch_inverses(ctx, D));
     TRY(pack_fast(ctx, D));
     TRY(make_f32(ctx, D));
+    TRY(pack_fused(ctx, D));
   }
   TRY(build_coarse(ctx));
   TRY(build_dense_coarse(ctx));
@@ -1758,6 +1891,7 @@ void hdgmg_default_opts(hdgmg_opts* o) {
   o->additive = 0;
   o->patch_relax = 0;
   o->patch_smooth = 0;
+  o->fused_phase = 1;
 }
 
 const char* hdgmg_last_error(const hdgmg_ctx* ctx) {
@@ -1854,7 +1988,8 @@ hdgmg_status hdgmg_setup(const hdgmg_mesh* mesh, int k, double beta, const doubl
       ctx->opts.transpose > 1 || (ctx->opts.transpose && !ctx->opts.oseen) || ctx->opts.coarse_dense < 0 ||
       ctx->opts.coarse_dense > 1 || ctx->opts.rec_wide < 0 || ctx->opts.rec_wide > 1 || ctx->opts.smoother < 0 ||
       ctx->opts.smoother > 1 || ctx->opts.additive < 0 || ctx->opts.additive > 1 || ctx->opts.patch_relax < 0 ||
-      ctx->opts.patch_relax > 2 || ctx->opts.patch_smooth < 0 || ctx->opts.patch_smooth > 2) {
+      ctx->opts.patch_relax > 2 || ctx->opts.patch_smooth < 0 || ctx->opts.patch_smooth > 2 ||
+      ctx->opts.fused_phase < 0 || ctx->opts.fused_phase > 1) {
     g_setup_error = "invalid options";
     delete ctx;
     return HDGMG_EINVAL;
@@ -1944,6 +2079,7 @@ hdgmg_status hdgmg_setup(const hdgmg_mesh* mesh, int k, double beta, const doubl
     return st;
   };
   if ((s = upload_level(ctx, LF, k + 1, ctx->K))) return fail(s);
+  if (ctx->opts.fused_phase && (s = setup_fused(ctx, LF, ctx->K))) return fail(s);
   // per-colour byte model of the order-k relaxation, from its own patches
   ctx->relax_bytes.resize(LF.ncol);
   for (int c = 0; c < LF.ncol; ++c) ctx->relax_bytes[c] = gs_phase_bytes(LF, k + 1, c);
@@ -1956,8 +2092,10 @@ hdgmg_status hdgmg_setup(const hdgmg_mesh* mesh, int k, double beta, const doubl
   }
   if ((s = upload(ctx, &ctx->K.nu, ctx->nu_fine))) return fail(s);
   ctx->cr.resize(ctx->J);
-  for (int l = 0; l < ctx->J; ++l)
+  for (int l = 0; l < ctx->J; ++l) {
     if ((s = upload_level(ctx, ctx->lv[l], 1, ctx->cr[l]))) return fail(s);
+    if (ctx->opts.fused_phase && (s = setup_fused(ctx, ctx->lv[l], ctx->cr[l]))) return fail(s);
+  }
   {
     std::vector<std::vector<double>> nul;
     level_viscosities(ctx->lv, ctx->nu_fine, nul);
@@ -2089,7 +2227,8 @@ hdgmg_status hdgmg_assemble(hdgmg_ctx* ctx) {
       double sw = 0.0;
       for (int c = 0; c < (int)K.colour_ptr.size() - 1; ++c) sw += phase_bytes(ctx, K, -1, c);
       const double res = K.fast ? K.bytes_cell_vc + K.bytes_sum : ctx->apply_bytes * (K.f32 ? 0.5 : 1.0);
-      v += 2.0 * o.m_relax * sw - (K.fast ? K.bytes_cell_vc : 0.0) + res;  // sweeps, residual
+      const double first = K.fused ? K.bytes_fused_vc[0] - K.bytes_relax_vc[0] : K.fast ? K.bytes_cell_vc : 0.0;
+      v += 2.0 * o.m_relax * sw - first + res;  // sweeps, residual
       v += 2.0 * K.ndof * 8.0;                                                 // the mode-0 transfers
     }
     double visits = 1.0, m_l = o.m_smooth;
@@ -2109,7 +2248,8 @@ hdgmg_status hdgmg_assemble(hdgmg_ctx* ctx) {
                           : (double)D.nc * 36 * ws + (D.nc * 6.0 + 2.0 * D.ndof) * 8.0;
       double trn = 2.0 * (ctx->tr[l].nnz * (4.0 + ws) + (ctx->tr[l].nfine + ctx->tr[l].ncoarse) * 8.0);
       const double zero_starts = l == ctx->J - 1 ? 1.0 : visits / o.cycle;
-      v += visits * (2.0 * m_l * sw + res + trn) - (D.fast && !D.rec ? zero_starts * D.bytes_cell_vc : 0.0);
+      const double first = D.fused ? D.bytes_fused_vc[0] - D.bytes_relax_vc[0] : D.fast && !D.rec ? D.bytes_cell_vc : 0.0;
+      v += visits * (2.0 * m_l * sw + res + trn) - zero_starts * first;
       visits *= o.cycle;
       m_l *= o.vcycle_growth;
     }

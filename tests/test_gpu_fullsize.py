@@ -185,6 +185,36 @@ def test_preconditioner_symmetric_positive(solvers):
     assert abs(a12 - a21) <= 1e-11 * np.sqrt(a11 * a22), (a12, a21, a11, a22)
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_fused_colour_phase_matches_the_pair(solvers, prec):
+    """The default order-k colour phase (one launch per colour that forms
+    each patch residual from the patch's own cells) against the
+    cell-apply / patch-relaxation pair it replaces: the same MG_hp up to the
+    summation order of the residual rows, and no order-k cell apply in the
+    colour phases (the pair has one per phase after the first)."""
+    import paper_2303_06762_amd as hd
+    c, t = synth.kuhn_square(4)
+    _note(f"[fullsize] fused colour phase vs pair, vcycle_precision {prec}")
+    pair = hd.Solver(c, t, NREF, K_ORDER, BETA, NU, GAMMA, atol=0.0, vcycle_precision=prec, fused_phase=0)
+    pair.assemble()
+    fused = solvers[prec]
+    r = dev(synth.uniform_pm1(23, 0, (fused.n_skel,)))
+    launches = {}
+    z = {}
+    for name, s in (("fused", fused), ("pair", pair)):
+        s.timer(1)
+        z[name] = s.precondition(r).clone()
+        launches[name] = s.timer_read(1)[1]
+        s.timer(1, False)
+    pair.close()
+    diff = (torch.linalg.norm(z["fused"] - z["pair"]) / torch.linalg.norm(z["pair"])).item()
+    _note(f"  rel. difference {diff:.2e}, order-k cell applies {launches}")
+    assert diff <= 1e-12, diff
+    # the pair applies the cells in every colour phase but the first one from
+    # zero: 2 m_relax n_colours - 1 = 5 more order-k cell applies
+    assert launches["pair"] - launches["fused"] == 5, launches
+
+
 def test_full_solve_at_sampled_facets_and_cells(setting, solvers):
     """AL-Uzawa + flexible CG: the saddle-point residual S lambda - D^T p - g
     at sampled facets equals the last inner residual (the Uzawa update

@@ -32,12 +32,23 @@ def jittered_square(n, seed, amp=0.2):
     return c, t
 
 
+def boundary_fan(n=7):
+    """n triangles around the boundary vertex (0.5, 0) of a half disc: after
+    red refinement that vertex keeps n - 1 interior edges and n cells (a
+    seven-cell vertex patch for n = 7, the largest the fused colour phase
+    takes)."""
+    th = np.linspace(np.pi, 0.0, n + 1)
+    c = np.vstack([[0.5, 0.0], np.c_[0.5 + 0.5 * np.cos(th), 0.5 * np.sin(th)]])
+    t = np.array([[0, i + 2, i + 1] for i in range(n)])  # counterclockwise
+    return c, t
+
+
 _ORACLES = {}
 
 
 def oracle_setup(key, coords, cells, n_refine, k, nu, beta, gamma, **kw):
     kw = {a: b for a, b in kw.items()
-          if a not in ("coarse_dofs", "stream_dofs", "coarse_dense", "rec_wide")}  # layout only
+          if a not in ("coarse_dofs", "stream_dofs", "coarse_dense", "rec_wide", "fused_phase")}  # layout only
     if key not in _ORACLES:
         _ORACLES[key] = solver.Setup(coords, cells, n_refine, k, nu, beta, gamma, **kw)
     return _ORACLES[key]
@@ -95,15 +106,27 @@ CASES = {
     "k2_stream": (lambda: synth.kuhn_square(4), 2, 2, 1.0, 1.0, 1e2, dict(stream_dofs=0, coarse_dofs=400)),
     "k3_stream": (lambda: synth.kuhn_square(4), 1, 3, 1.0, 0.0, 1e4, dict(stream_dofs=0)),
     "k4_stream": (lambda: jittered_square(4, 5), 1, 4, 0.7, 2.0, 1e2, dict(stream_dofs=0)),
+    # k = 1, 2 above run the fused colour phase; the cell-apply / relaxation
+    # pair it replaces, and the fused phase with a seven-cell boundary patch
+    "k1_stream_pair": (lambda: synth.kuhn_square(4), 1, 1, 1.0, 1.0, 1e2, dict(stream_dofs=0, fused_phase=0)),
+    "k2_stream_pair": (lambda: jittered_square(4, 3), 2, 2, 1.0, 1.0, 1e2,
+                       dict(stream_dofs=0, coarse_dofs=400, fused_phase=0)),
+    "k2_fan_stream": (lambda: boundary_fan(7), 2, 2, 0.9, 1.0, 1e2, dict(stream_dofs=0)),
+    "k1_fan_stream": (lambda: boundary_fan(7), 2, 1, 1.0, 0.5, 1e3, dict(stream_dofs=0, coarse_dofs=0)),
     # streaming layout on every level, but the lowest-order levels outside the
-    # coarse kernel smooth with the record kernel (residuals stay streamed)
-    "k1_stream_rec": (lambda: synth.kuhn_square(4), 2, 1, 1.0, 1.0, 1e2, dict(stream_dofs=1, coarse_dofs=200)),
-    "k2_stream_rec": (lambda: synth.kuhn_square(4), 2, 2, 0.8, 0.5, 1e2, dict(stream_dofs=1, coarse_dofs=0)),
+    # coarse kernel smooth with the record kernel (residuals stay streamed;
+    # without the fused phase, which would take those levels)
+    "k1_stream_rec": (lambda: synth.kuhn_square(4), 2, 1, 1.0, 1.0, 1e2,
+                      dict(stream_dofs=1, coarse_dofs=200, fused_phase=0)),
+    "k2_stream_rec": (lambda: synth.kuhn_square(4), 2, 2, 0.8, 0.5, 1e2,
+                      dict(stream_dofs=1, coarse_dofs=0, fused_phase=0)),
     # the 32-bit record form (levels beyond 65535 facets) forced on every level
     "k2_stream_rec_wide": (lambda: synth.kuhn_square(4), 2, 2, 0.8, 0.5, 1e2,
-                           dict(stream_dofs=1, coarse_dofs=0, rec_wide=1)),
+                           dict(stream_dofs=1, coarse_dofs=0, rec_wide=1, fused_phase=0)),
     "k1_rec_wide_split": (lambda: synth.kuhn_square(4), 2, 1, 1.0, 1.0, 1e2,
-                          dict(stream_dofs=1, coarse_dofs=200, rec_wide=1)),
+                          dict(stream_dofs=1, coarse_dofs=200, rec_wide=1, fused_phase=0)),
+    # the fused colour phase on the order-k and every lowest-order level
+    "k2_fused_all": (lambda: synth.kuhn_square(4), 2, 2, 0.8, 0.5, 1e2, dict(stream_dofs=1, coarse_dofs=0)),
 }
 
 
