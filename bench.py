@@ -35,16 +35,17 @@ KCLASS3 = {0: "order-k edge-patch Gauss-Seidel, one colour (k_patch_gs3)",
            1: "order-k skeleton apply S_K x_K (k_cell_apply3 + k_face_gather3)",
            2: "lowest-order edge-patch Gauss-Seidel phases (k_patch_gs3, m_F = 1)",
            3: "MG_hp"}
-KCLASS = {0: "order-k vertex-patch relaxation, one colour (k_patch_relax)",
-          1: "order-k cell apply S_K x_K (k_cell_apply)",
-          2: "lowest-order smoothing phases on launched levels (k_gs / streaming pair)"}
+KCLASS = {0: "order-k vertex-patch Gauss-Seidel, one colour phase (k_patch_gs_fused; "
+             "k_patch_relax_wave for the first phase from zero)",
+          1: "order-k cell apply S_K x_K (k_cell_apply: the residual and Krylov applies)",
+          2: "lowest-order smoothing phases on launched levels (k_patch_gs_fused on streamed levels, "
+             "k_gs_records on the others)"}
 # Class 4: MG_h on the coarse levels -- at the V-cycle's entry level the
 # operator tabulated at assembly (one dense GEMV), else the single-workgroup
 # kernel.
 COARSE_CLASS = "coarse MG_h: tabulated operator (k_gemv_rows) / single-workgroup kernel (k_coarse_cycle)"
-# The roofline object reports the order-k cell apply: the HBM-bound kernel
-# that runs most often (every Gauss-Seidel colour phase and every Krylov
-# apply read all cell blocks).
+# The 2D line reports the order-k cell apply (every Krylov apply and every
+# V-cycle residual read all cell blocks) and the colour phase.
 ROOF_CLASS = 1
 
 def _oracle_worker(args):
@@ -587,6 +588,10 @@ def stokes2d_line(hd, synth, torch, np, a):
             "vcycle": vcyc(m64), "kernel_classes": classes(m64["tm"]),
             "cell_apply": {"avg_us": 1e3 * ms / n_l, "algorithmic_bytes_per_launch": by / n_l,
                            "GB_per_s": by / n_l / (ms / n_l * 1e-3) / 1e9},
+            "colour_phase": {"avg_us": 1e3 * m64["tm"][0][0] / max(m64["tm"][0][1], 1),
+                             "algorithmic_bytes_per_launch": m64["tm"][0][2] / max(m64["tm"][0][1], 1),
+                             "GB_per_s": m64["tm"][0][2] / max(m64["tm"][0][0] * 1e-3, 1e-30) / 1e9,
+                             "kernel": KCLASS[0]},
             "setup_s": m64["t_setup"], "assemble_s": m64["t_assemble"],
             "mixed": {"value": n * a.steps2d / m32["T"], "iterations": m32["its"],
                       "rel_diff_vs_fp64_solution": m32["err"], "vcycle": vcyc(m32),
