@@ -669,15 +669,6 @@ __global__ void k_ell_spmv_g(int n, int w, const int* __restrict__ ci, const TS*
   }
 }
 
-template <typename TS>
-__global__ void k_gemv_dense(int n, const TS* __restrict__ A, const double* __restrict__ x,
-                             double* __restrict__ y) {
-  int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
-  double s = 0.0;
-  for (int c = 0; c < n; ++c) s += (double)A[(long)c * n + r] * x[c];  // column-major
-  y[r] = s;
-}
 
 // y = A x for a dense row-major A (n x n, storage TS, row stride ld: a
 // multiple of 4, zero-padded), a wavefront per row: each lane reads four
@@ -1075,11 +1066,6 @@ template void launch_ell_spmv<double>(hipStream_t, int, int, const int*, const d
 template void launch_ell_spmv<float>(hipStream_t, int, int, const int*, const float*, const double*, double*,
                                      double, double*);
 template <typename TS>
-void launch_gemv_dense(hipStream_t st, int n, const TS* A, const double* x, double* y) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_gemv_dense<TS>, dim3(nblk(n)), dim3(TPB), 0, st, n, A, x, y);
-}
-template <typename TS>
 void launch_gemv_rows(hipStream_t st, int n, int ld, const TS* A, const double* x, double* y) {
   if (n > 0) hipLaunchKernelGGL(k_gemv_rows<TS>, dim3((n + 3) / 4), dim3(256), 0, st, n, ld, A, x, y);
 }
@@ -1096,8 +1082,6 @@ void launch_identity(hipStream_t st, int n, double* out) {
   const long nn = (long)n * n;
   if (nn > 0) hipLaunchKernelGGL(k_identity, dim3(nblk(nn)), dim3(TPB), 0, st, n, out);
 }
-template void launch_gemv_dense<double>(hipStream_t, int, const double*, const double*, double*);
-template void launch_gemv_dense<float>(hipStream_t, int, const float*, const double*, double*);
 void launch_fill(hipStream_t st, long n, double v, double* x) {
   if (n > 0) hipLaunchKernelGGL(k_fill, dim3(nblk(n)), dim3(TPB), 0, st, n, v, x);
 }

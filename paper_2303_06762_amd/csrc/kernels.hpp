@@ -133,8 +133,6 @@ void launch_mode0_add(hipStream_t st, int nint, int m, const double* u0, double*
 template <typename TS>
 void launch_ell_spmv(hipStream_t st, int n, int w, const int* ci, const TS* v, const double* x, double* y,
                      double beta_y, double* zero_out = nullptr);
-template <typename TS>
-void launch_gemv_dense(hipStream_t st, int n, const TS* A, const double* x, double* y);
 // y = A x, A dense row-major n x n in storage TS with row stride ld (a
 // multiple of 4, rows zero-padded; a wavefront per row, 16-byte loads)
 template <typename TS>

@@ -71,7 +71,11 @@ struct Ctx3 {
   std::vector<DevLev3> cr;
   std::vector<DevTr3> tr;
   double* coarse_inv = nullptr;
-  float* coarse_inv32 = nullptr;
+  // the coarsest inverse row by row (rows padded to ld0 words) for the
+  // wavefront-per-row GEMV, in the V-cycle's storage precision
+  double* coarse_rows = nullptr;
+  float* coarse_rows32 = nullptr;
+  int ld0 = 0;
   int n0 = 0;
   double *x = nullptr, *r = nullptr, *r_old = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
   double *b = nullptr, *gvec = nullptr, *lam = nullptr, *p0 = nullptr, *sc = nullptr, *part = nullptr;
@@ -703,9 +707,9 @@ void mg_h(Ctx3* c, int l, int m_l) {
   DevLev3& D = c->cr[l];
   if (l == 0) {
     if (f32(c))
-      launch_gemv_dense<float>(c->st, c->n0, c->coarse_inv32, D.g, D.u);
+      launch_gemv_rows<float>(c->st, c->n0, c->ld0, c->coarse_rows32, D.g, D.u);
     else
-      launch_gemv_dense<double>(c->st, c->n0, c->coarse_inv, D.g, D.u);
+      launch_gemv_rows<double>(c->st, c->n0, c->ld0, c->coarse_rows, D.g, D.u);
     return;
   }
   for (int s = 0; s < m_l; ++s) sweep(c, D, D.u, D.g, true, 2);
@@ -1148,10 +1152,17 @@ hdgmg_status d3_assemble(Ctx3* c) {
       launch_f32_copy(c->st, np_, T.Pv, T.Pv32);
       launch_f32_copy(c->st, nr_, T.Rv, T.Rv32);
     }
-    if (!c->coarse_inv32) TRY3(dalloc(c, &c->coarse_inv32, (size_t)std::max(c->n0, 1) * std::max(c->n0, 1)));
-    launch_f32_copy(c->st, (long)c->n0 * c->n0, c->coarse_inv, c->coarse_inv32);
     HIPC3(hipStreamSynchronize(c->st));
   }
+  c->ld0 = (c->n0 + 3) / 4 * 4;
+  if (f32(c)) {
+    if (!c->coarse_rows32) TRY3(dalloc(c, &c->coarse_rows32, (size_t)std::max(c->n0, 1) * std::max(c->ld0, 4)));
+    launch_transpose_to<float>(c->st, c->n0, c->ld0, c->coarse_inv, c->coarse_rows32);
+  } else {
+    if (!c->coarse_rows) TRY3(dalloc(c, &c->coarse_rows, (size_t)std::max(c->n0, 1) * std::max(c->ld0, 4)));
+    launch_transpose_to<double>(c->st, c->n0, c->ld0, c->coarse_inv, c->coarse_rows);
+  }
+  HIPC3(hipGetLastError());
   // algorithmic bytes of one V-cycle in the storage the preconditioner reads
   const double b = f32(c) ? 4.0 : 8.0;
   double vb = 0.0;

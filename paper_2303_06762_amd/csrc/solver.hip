@@ -228,6 +228,11 @@ struct hdgmg_ctx {
   std::vector<DevTransfer> tr;
   double* coarse_inv = nullptr;
   float* coarse_inv32 = nullptr;
+  // the coarsest inverse row by row (rows padded to ld0 words) for the
+  // wavefront-per-row GEMV, in the V-cycle's storage precision
+  double* coarse_rows = nullptr;
+  float* coarse_rows32 = nullptr;
+  int ld0 = 0;
   int n0 = 0;
   // Krylov / Uzawa vectors
   double *x = nullptr, *r = nullptr, *r_old = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
@@ -906,9 +911,9 @@ void mg_h(hdgmg_ctx* ctx, int l, int m_l, bool u_zero) {
   }
   if (l == 0) {
     if (vc_f32(ctx))
-      launch_gemv_dense<float>(ctx->st, ctx->n0, ctx->coarse_inv32, D.g, D.u);
+      launch_gemv_rows<float>(ctx->st, ctx->n0, ctx->ld0, ctx->coarse_rows32, D.g, D.u);
     else
-      launch_gemv_dense<double>(ctx->st, ctx->n0, ctx->coarse_inv, D.g, D.u);
+      launch_gemv_rows<double>(ctx->st, ctx->n0, ctx->ld0, ctx->coarse_rows, D.g, D.u);
     return;
   }
   for (int s = 0; s < m_l; ++s) sweep(ctx, D, D.u, D.g, true, l, u_zero && s == 0);
@@ -1253,6 +1258,15 @@ hdgmg_status build_transfers(hdgmg_ctx* ctx) {
   ctx->n0 = 2 * ctx->lv[0].nint;
   TRY(upload(ctx, &ctx->coarse_inv, inv));
   if (vc_f32(ctx)) TRY(upload_f32(ctx, &ctx->coarse_inv32, inv));
+  ctx->ld0 = (ctx->n0 + 3) / 4 * 4;
+  if (vc_f32(ctx)) {
+    TRY(dalloc(ctx, &ctx->coarse_rows32, (size_t)std::max(ctx->n0, 1) * std::max(ctx->ld0, 4)));
+    launch_transpose_to<float>(ctx->st, ctx->n0, ctx->ld0, ctx->coarse_inv, ctx->coarse_rows32);
+  } else {
+    TRY(dalloc(ctx, &ctx->coarse_rows, (size_t)std::max(ctx->n0, 1) * std::max(ctx->ld0, 4)));
+    launch_transpose_to<double>(ctx->st, ctx->n0, ctx->ld0, ctx->coarse_inv, ctx->coarse_rows);
+  }
+  HIPC(hipGetLastError());
   return HDGMG_OK;
 }
 
