@@ -43,6 +43,12 @@ struct DevLev3 {
   // entries, and vector words (FP64)
   std::vector<double> phase_S, phase_P, phase_V;
   double *u = nullptr, *g = nullptr, *r = nullptr, *yK = nullptr;
+  // order-k level: the twelve mode-0 rows of every cell block ([nK][12][nc],
+  // in the V-cycle's storage, FP32 without the AL term) and their products,
+  // for the residual that MG_hp restricts to the lowest-order space
+  double* S0 = nullptr;
+  float* S0_32 = nullptr;
+  double* y0K = nullptr;
 };
 
 struct DevTr3 {
@@ -743,8 +749,11 @@ void mg_hp(Ctx3* c, const double* r, double* z) {
   } else {
     launch_fill(c->st, KL.ndof, 0.0, z);
     for (int s = 0; s < c->opts.m_relax; ++s) sweep(c, KL, z, r, true, 0);
-    apply_k(c, z, KL.r, -1.0, r, true);
-    launch_mode0_extract3(c->st, KL.nint, KL.mF, KL.r, DJ.g, DJ.u);
+    // Pi_k^0 (r - A z): only the mode-0 rows of A z
+    if (f32(c))
+      launch_mode0_residual3<float>(c->st, view32(c, KL), KL.S0_32, z, KL.y0K, r, DJ.g, DJ.u);
+    else
+      launch_mode0_residual3<double>(c->st, view<double>(KL, KL.S), KL.S0, z, KL.y0K, r, DJ.g, DJ.u);
     mg_h(c, c->J - 1, c->opts.m_smooth);
     launch_mode0_add3(c->st, KL.nint, KL.mF, DJ.u, z);
     for (int s = 0; s < c->opts.m_relax; ++s) sweep(c, KL, z, r, false, 0);
@@ -1163,6 +1172,19 @@ hdgmg_status d3_assemble(Ctx3* c) {
     launch_transpose_to<double>(c->st, c->n0, c->ld0, c->coarse_inv, c->coarse_rows);
   }
   HIPC3(hipGetLastError());
+  if (c->k > 0) {
+    DevLev3& D = c->K;
+    const size_t n0r = (size_t)std::max(D.nc, 1) * 12 * D.nK;
+    if (!D.y0K) TRY3(dalloc(c, &D.y0K, (size_t)std::max(D.nc, 1) * 12));
+    if (f32(c)) {
+      if (!D.S0_32) TRY3(dalloc(c, &D.S0_32, n0r));
+      launch_pack_mode0_rows3<float>(c->st, D.nc, D.mF, D.S32, D.S0_32);
+    } else {
+      if (!D.S0) TRY3(dalloc(c, &D.S0, n0r));
+      launch_pack_mode0_rows3<double>(c->st, D.nc, D.mF, D.S, D.S0);
+    }
+    HIPC3(hipGetLastError());
+  }
   // algorithmic bytes of one V-cycle in the storage the preconditioner reads
   const double b = f32(c) ? 4.0 : 8.0;
   double vb = 0.0;
@@ -1172,7 +1194,12 @@ hdgmg_status d3_assemble(Ctx3* c) {
     return s;
   };
   auto level_res = [&](const DevLev3& D) { return b * D.nc * (double)D.nK * D.nK + 8.0 * 4.0 * D.ndof; };
-  if (c->k > 0) vb += 2.0 * c->opts.m_relax * level_sweep(c->K) + level_res(c->K);
+  // the order-k residual: only its mode-0 rows (x_K gathered per cell, the
+  // twelve rows' products written and read, b's and g0's mode-0 entries)
+  auto res0 = [&](const DevLev3& D) {
+    return b * D.nc * 12.0 * D.nK + 8.0 * (D.nc * (double)D.nK + 3.0 * D.nc * 12.0 + 3.0 * 3.0 * D.nint);
+  };
+  if (c->k > 0) vb += 2.0 * c->opts.m_relax * level_sweep(c->K) + (c->opts.additive ? 0.0 : res0(c->K));
   int m = c->opts.m_smooth;
   for (int l = c->J - 1; l >= 1; --l) {
     vb += 2.0 * m * level_sweep(c->cr[l]) + level_res(c->cr[l]);
@@ -1190,8 +1217,10 @@ hdgmg_status d3_assemble(Ctx3* c) {
     return D.nc * tri(D.nK) * b + pb * (pinv64(c, D) ? 8.0 : b) + 3.0 * 8.0 * D.ndof;
   };
   auto res_c = [&](const DevLev3& D) { return D.nc * tri(D.nK) * b + 3.0 * 8.0 * D.ndof; };
+  // the order-k residual enters MG_hp only through its mode-0 rows
+  auto res0_c = [&](const DevLev3& D) { return D.nc * 12.0 * D.nK * b + 3.0 * 8.0 * 3.0 * D.nint; };
   double vc = 0.0;
-  if (c->k > 0) vc += 2.0 * c->opts.m_relax * sweep_c(c->K) + res_c(c->K);
+  if (c->k > 0) vc += 2.0 * c->opts.m_relax * sweep_c(c->K) + (c->opts.additive ? 0.0 : res0_c(c->K));
   double vis = 1.0, ml = c->opts.m_smooth;
   for (int l = c->J - 1; l >= 1; --l) {
     vc += vis * (2.0 * ml * sweep_c(c->cr[l]) + res_c(c->cr[l]));

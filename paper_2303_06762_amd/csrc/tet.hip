@@ -710,6 +710,80 @@ __global__ void __launch_bounds__(64) k_cell_apply3(Level3View<TS> L, const doub
   }
 }
 
+// The twelve mode-0 rows of every cell block (local face i, component q:
+// row i m3 + q mF), cell-minor so that a wavefront's consecutive cells read
+// consecutive words: entry (row i * 3 + q, column col) of cell K at
+// S0[(col * 12 + i * 3 + q) * nc + K].
+template <typename TS>
+__global__ void k_pack_mode0_rows3(int nc, int mF, const TS* __restrict__ S, TS* __restrict__ S0) {
+  const int nK = 12 * mF, m3 = 3 * mF;
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)nc * nK) return;
+  const int col = (int)(t / nc), K = (int)(t % nc);
+#pragma unroll
+  for (int r = 0; r < 12; ++r)
+    S0[((long)col * 12 + r) * nc + K] = S[(long)K * nK * nK + sblk((r / 3) * m3 + (r % 3) * mF, col, m3, nK)];
+}
+
+// Mode-0 rows of S_K x_K for M0_CELLS cells per workgroup: x_K of the cells
+// into LDS (rows padded by one word against bank conflicts), then thread
+// (row r, cell j) forms row r of cell j's product from S0 with eight loads
+// in flight (a wavefront reads two rows of 32 consecutive cells per word).
+// With al > 0 (S0 without its augmented-Lagrangian term) the term is added
+// apart on the normal rows, as in the full apply.
+constexpr int M0_CELLS = 32;
+template <typename TS>
+__global__ void __launch_bounds__(12 * M0_CELLS) k_cell_mode0_3(Level3View<TS> L, const TS* __restrict__ S0,
+                                                                const double* __restrict__ x,
+                                                                double* __restrict__ y0K) {
+  __shared__ double xs[M0_CELLS][12 * MF3MAX + 1];
+  const int nK = L.nK, m3 = 3 * L.mF, nc = L.nc;
+  const int K0 = blockIdx.x * M0_CELLS, tid = threadIdx.x;
+  for (int e = tid; e < M0_CELLS * nK; e += 12 * M0_CELLS) {
+    const int j = e / nK, i = e % nK, K = min(K0 + j, nc - 1);
+    const int dof = L.cell_dofs[4 * K + i / m3];
+    xs[j][i] = dof < 0 ? 0.0 : x[(long)dof * m3 + i % m3];
+  }
+  __syncthreads();
+  const int j = tid % M0_CELLS, r = tid / M0_CELLS, K = K0 + j;
+  if (K >= nc) return;
+  const TS* a = S0 + (long)r * nc + K;
+  const long step = 12L * nc;  // next column
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int col = 0;
+  for (; col + 8 <= nK; col += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = (double)a[(long)(col + u) * step];
+    a0 += v[0] * xs[j][col] + v[4] * xs[j][col + 4];
+    a1 += v[1] * xs[j][col + 1] + v[5] * xs[j][col + 5];
+    a2 += v[2] * xs[j][col + 2] + v[6] * xs[j][col + 6];
+    a3 += v[3] * xs[j][col + 3] + v[7] * xs[j][col + 7];
+  }
+  for (; col < nK; ++col) a0 += (double)a[(long)col * step] * xs[j][col];
+  double acc = (a0 + a1) + (a2 + a3);
+  if (L.al > 0.0 && r % 3 == 0) {
+    double dx = 0.0;
+    for (int q = 0; q < 4; ++q) dx += L.cdiv[4 * K + q] * xs[j][q * m3];
+    acc += L.al / L.vol[K] * L.cdiv[4 * K + r / 3] * dx;
+  }
+  y0K[(long)K * 12 + r] = acc;
+}
+
+// g0 = mode 0 of (b - A x) from the cells' mode-0 rows (face fi, component
+// q: the rows of its two cells); zero_out (if not null) zeroed alike.
+__global__ void k_mode0_gather3(int nint, int mF, const int* __restrict__ fcell, const int* __restrict__ floc,
+                                const double* __restrict__ y0K, const double* __restrict__ b,
+                                double* __restrict__ g0, double* __restrict__ zero_out) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 3L * nint) return;
+  const int fi = (int)(t / 3), q = (int)(t % 3);
+  double acc = 0.0;
+  for (int s = 0; s < 2; ++s) acc += y0K[(long)fcell[2 * fi + s] * 12 + floc[2 * fi + s] * 3 + q];
+  g0[t] = b[(long)fi * 3 * mF + q * mF] - acc;
+  if (zero_out) zero_out[t] = 0.0;
+}
+
 __global__ void k_blocks_to_dense(int nc, int m3, const double* __restrict__ in, double* __restrict__ out) {
   const int nK = 4 * m3;
   const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1007,6 +1081,30 @@ void launch_cell_apply3(hipStream_t st, Level3View<TS> L, const double* x, doubl
 }
 template void launch_cell_apply3<double>(hipStream_t, Level3View<double>, const double*, double*);
 template void launch_cell_apply3<float>(hipStream_t, Level3View<float>, const double*, double*);
+
+template <typename TS>
+void launch_pack_mode0_rows3(hipStream_t st, int nc, int mF, const TS* S, TS* S0) {
+  const long n = (long)nc * 12 * mF;
+  if (n > 0) hipLaunchKernelGGL(k_pack_mode0_rows3<TS>, dim3(blocks(n, 256)), dim3(256), 0, st, nc, mF, S, S0);
+}
+template void launch_pack_mode0_rows3<double>(hipStream_t, int, int, const double*, double*);
+template void launch_pack_mode0_rows3<float>(hipStream_t, int, int, const float*, float*);
+
+template <typename TS>
+void launch_mode0_residual3(hipStream_t st, Level3View<TS> L, const TS* S0, const double* x, double* y0K,
+                            const double* b, double* g0, double* zero_out) {
+  if (L.nc > 0)
+    hipLaunchKernelGGL(k_cell_mode0_3<TS>, dim3((L.nc + M0_CELLS - 1) / M0_CELLS), dim3(12 * M0_CELLS), 0, st, L, S0,
+                       x, y0K);
+  const long n = 3L * L.nint;
+  if (n > 0)
+    hipLaunchKernelGGL(k_mode0_gather3, dim3(blocks(n, 256)), dim3(256), 0, st, L.nint, L.mF, L.fcell, L.floc, y0K,
+                       b, g0, zero_out);
+}
+template void launch_mode0_residual3<double>(hipStream_t, Level3View<double>, const double*, const double*, double*,
+                                             const double*, double*, double*);
+template void launch_mode0_residual3<float>(hipStream_t, Level3View<float>, const float*, const double*, double*,
+                                            const double*, double*, double*);
 
 void launch_blocks_to_dense(hipStream_t st, int nc, int m3, const double* in, double* out) {
   const long n = (long)nc * 16 * m3 * m3;

@@ -127,6 +127,16 @@ template <typename TS>
 void launch_cell_apply3(hipStream_t st, Level3View<TS> L, const double* x, double* yK);
 void launch_face_gather3(hipStream_t st, int nint, int mF, int nK, const int* fcell, const int* floc,
                          const double* yK, double alpha, const double* b, double* y);
+// The twelve mode-0 rows (local face i, component q) of every cell block of
+// S (sblk layout), as S0 [nK][12][nc] (cell-minor).
+template <typename TS>
+void launch_pack_mode0_rows3(hipStream_t st, int nc, int mF, const TS* S, TS* S0);
+// g0 = mode 0 of (b - A x) [nint][3] from S0 (only the mode-0 rows of the
+// cell products: y0K [nc][12] scratch; L.al > 0: the AL term apart);
+// zero_out (if not null) zeroed over the same 3 nint entries.
+template <typename TS>
+void launch_mode0_residual3(hipStream_t st, Level3View<TS> L, const TS* S0, const double* x, double* y0K,
+                            const double* b, double* g0, double* zero_out);
 // Edge-patch inverses (column-major, pinv + poff[p]) of the patches
 // [p0, p0 + np): a workgroup per patch, Gauss-Jordan with partial pivoting
 // in global workspace (ws: np * ns_max * 2 * ns_max doubles).
