@@ -591,6 +591,75 @@ __global__ void __launch_bounds__(256) k_patch_correct(const int* __restrict__ p
   }
 }
 
+// The six mode-0 rows of every order-k cell block (local facet i, component
+// c: row (i 2 + c) m), cell-minor: entry (row i 2 + c, column col) of cell K
+// at S0[(col * 6 + i * 2 + c) * nc + K]; S full row-major [nc][nK][nK].
+template <typename TS>
+__global__ void k_pack_mode0_rows(int nc, int m, const double* __restrict__ S, TS* __restrict__ S0) {
+  const int nK = 6 * m;
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)nc * nK) return;
+  const int col = (int)(t / nc), K = (int)(t % nc);
+#pragma unroll
+  for (int r = 0; r < 6; ++r) S0[((long)col * 6 + r) * nc + K] = (TS)S[((long)K * nK + r * m) * nK + col];
+}
+
+// Mode-0 rows of S_K x_K, M0_CELLS2 cells per workgroup: x_K into LDS (rows
+// padded by one word), then thread (row r, cell j) forms its row from S0 with
+// eight loads in flight (a wavefront reads one row of 64 consecutive cells
+// per word).
+constexpr int M0_CELLS2 = 64;
+template <typename TS>
+__global__ void __launch_bounds__(6 * M0_CELLS2) k_cell_mode0(int nc, int m, const int* __restrict__ cell_dofs,
+                                                              const TS* __restrict__ S0,
+                                                              const double* __restrict__ x,
+                                                              double* __restrict__ y0K) {
+  __shared__ double xs[M0_CELLS2][6 * 5 + 1];
+  const int nK = 6 * m, m2 = 2 * m;
+  const int K0 = blockIdx.x * M0_CELLS2, tid = threadIdx.x;
+  for (int e = tid; e < M0_CELLS2 * nK; e += 6 * M0_CELLS2) {
+    const int j = e / nK, i = e % nK, K = min(K0 + j, nc - 1);
+    const int dof = cell_dofs[3 * K + i / m2];
+    xs[j][i] = dof < 0 ? 0.0 : x[(long)dof * m2 + i % m2];
+  }
+  __syncthreads();
+  const int j = tid % M0_CELLS2, r = tid / M0_CELLS2, K = K0 + j;
+  if (K >= nc) return;
+  const TS* a = S0 + (long)r * nc + K;
+  const long step = 6L * nc;  // next column
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int col = 0;
+  for (; col + 8 <= nK; col += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = (double)a[(long)(col + u) * step];
+    a0 += v[0] * xs[j][col] + v[4] * xs[j][col + 4];
+    a1 += v[1] * xs[j][col + 1] + v[5] * xs[j][col + 5];
+    a2 += v[2] * xs[j][col + 2] + v[6] * xs[j][col + 6];
+    a3 += v[3] * xs[j][col + 3] + v[7] * xs[j][col + 7];
+  }
+  for (; col < nK; ++col) a0 += (double)a[(long)col * step] * xs[j][col];
+  y0K[(long)K * 6 + r] = (a0 + a1) + (a2 + a3);
+}
+
+// g0 = mode 0 of (b - A x) from the cells' mode-0 rows (facet fi, component
+// c: the rows of its cells; a do-nothing facet has one); zero_out (if not
+// null) zeroed alike.
+__global__ void k_mode0_gather(int nint, int m, const int* __restrict__ fcell, const int* __restrict__ floc,
+                               const double* __restrict__ y0K, const double* __restrict__ b,
+                               double* __restrict__ g0, double* __restrict__ zero_out) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 2L * nint) return;
+  const int fi = (int)(t / 2), c = (int)(t % 2);
+  double acc = 0.0;
+  for (int s = 0; s < 2; ++s) {
+    const int K = fcell[2 * fi + s];
+    if (K >= 0) acc += y0K[(long)K * 6 + floc[2 * fi + s] * 2 + c];
+  }
+  g0[t] = b[t * m] - acc;
+  if (zero_out) zero_out[t] = 0.0;
+}
+
 __global__ void k_mode0_extract(int nint, int m, const double* __restrict__ r, double* __restrict__ g0,
                                 double* __restrict__ zero_out) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1034,6 +1103,28 @@ template void launch_patch_correct<float>(hipStream_t, const int*, const int*, c
                                           int, int, const double*, double*, double);
 template void launch_gs<double>(hipStream_t, LevelViewT<double>, int, int, double*, const double*);
 template void launch_gs<float>(hipStream_t, LevelViewT<float>, int, int, double*, const double*);
+template <typename TS>
+void launch_pack_mode0_rows(hipStream_t st, int nc, int m, const double* S, TS* S0) {
+  const long n = (long)nc * 6 * m;
+  if (n > 0) hipLaunchKernelGGL(k_pack_mode0_rows<TS>, dim3(nblk(n)), dim3(TPB), 0, st, nc, m, S, S0);
+}
+template void launch_pack_mode0_rows<double>(hipStream_t, int, int, const double*, double*);
+template void launch_pack_mode0_rows<float>(hipStream_t, int, int, const double*, float*);
+template <typename TS>
+void launch_mode0_residual(hipStream_t st, int nc, int nint, int m, const int* cell_dofs, const int* fcell,
+                           const int* floc, const TS* S0, const double* x, double* y0K, const double* b, double* g0,
+                           double* zero_out) {
+  if (nc > 0)
+    hipLaunchKernelGGL(k_cell_mode0<TS>, dim3((nc + M0_CELLS2 - 1) / M0_CELLS2), dim3(6 * M0_CELLS2), 0, st, nc, m,
+                       cell_dofs, S0, x, y0K);
+  if (nint > 0)
+    hipLaunchKernelGGL(k_mode0_gather, dim3(nblk(2L * nint)), dim3(TPB), 0, st, nint, m, fcell, floc, y0K, b, g0,
+                       zero_out);
+}
+template void launch_mode0_residual<double>(hipStream_t, int, int, int, const int*, const int*, const int*,
+                                            const double*, const double*, double*, const double*, double*, double*);
+template void launch_mode0_residual<float>(hipStream_t, int, int, int, const int*, const int*, const int*,
+                                           const float*, const double*, double*, const double*, double*, double*);
 void launch_mode0_extract(hipStream_t st, int nint, int m, const double* r, double* g0, double* zero_out) {
   if (nint <= 0) return;
   hipLaunchKernelGGL(k_mode0_extract, dim3(nblk(2L * nint)), dim3(TPB), 0, st, nint, m, r, g0, zero_out);

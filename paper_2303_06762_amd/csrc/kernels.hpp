@@ -128,6 +128,17 @@ void launch_to_f32(hipStream_t st, long n, const double* in, float* out);
 // null) is set to zero over the same 2 nint entries.
 void launch_mode0_extract(hipStream_t st, int nint, int m, const double* r, double* g0, double* zero_out = nullptr);
 void launch_mode0_add(hipStream_t st, int nint, int m, const double* u0, double* x);
+// The six mode-0 rows (local facet i, component c) of every order-k cell
+// block of S (full row-major, nK = 6 m <= 30) as S0 [nK][6][nc] (cell-minor).
+template <typename TS>
+void launch_pack_mode0_rows(hipStream_t st, int nc, int m, const double* S, TS* S0);
+// g0 = mode 0 of (b - A x) [2 nint] from S0, y0K [nc][6] scratch (only the
+// mode-0 rows of the cell products); zero_out (if not null) zeroed over the
+// same entries.
+template <typename TS>
+void launch_mode0_residual(hipStream_t st, int nc, int nint, int m, const int* cell_dofs, const int* fcell,
+                           const int* floc, const TS* S0, const double* x, double* y0K, const double* b, double* g0,
+                           double* zero_out);
 // y = A x + beta_y y for an ELL matrix (n rows, width w); zero_out (if not
 // null) is set to zero over the same n rows.
 template <typename TS>

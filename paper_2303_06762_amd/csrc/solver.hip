@@ -90,6 +90,12 @@ struct DevLevel {
   long sp_words = 0;      // words per cell of the streaming cell blocks
   double* Sp = nullptr;   // packed SoA cell blocks
   int* cdof = nullptr;    // [3][nc] 2*facet+side or -1
+  // order-k level: the six mode-0 rows of every cell block ([nK][6][nc], in
+  // the V-cycle's storage) and their products, for the residual that MG_hp
+  // restricts to the lowest-order space
+  double* S0 = nullptr;
+  float* S0_32 = nullptr;
+  double* y0K = nullptr;
   double* yF = nullptr;   // [nint][2][2m] per-side facet rows
   std::vector<int> npc;   // patches per colour
   std::vector<int*> pfc;  // per colour [FAST_NF][npc] facets
@@ -1005,8 +1011,13 @@ void mg_hp_body(hdgmg_ctx* ctx, const double* r, double* z) {
     return;
   }
   for (int s = 0; s < ctx->opts.m_relax; ++s) sweep(ctx, KL, z, r, true, -1, s == 0);
-  apply_k(ctx, z, KL.r, -1.0, r, true);
-  launch_mode0_extract(ctx->st, KL.nint, KL.m, KL.r, DJ.g, DJ.u);  // and DJ.u = 0
+  // Pi_k^0 (r - A z): only the mode-0 rows of A z (and DJ.u = 0)
+  if (vc_f32(ctx))
+    launch_mode0_residual<float>(ctx->st, KL.nc, KL.nint, KL.m, KL.cell_dofs, KL.fcell, KL.floc, KL.S0_32, z,
+                                 KL.y0K, r, DJ.g, DJ.u);
+  else
+    launch_mode0_residual<double>(ctx->st, KL.nc, KL.nint, KL.m, KL.cell_dofs, KL.fcell, KL.floc, KL.S0, z,
+                                  KL.y0K, r, DJ.g, DJ.u);
   mg_h(ctx, ctx->J - 1, ctx->opts.m_smooth, true);
   launch_mode0_add(ctx->st, KL.nint, KL.m, DJ.u, z);
   for (int s = 0; s < ctx->opts.m_relax; ++s) sweep(ctx, KL, z, r, false, -1);
@@ -1792,6 +1803,19 @@ hdgmg_status assemble_levels(hdgmg_ctx* ctx) {
   TRY(pack_fast(ctx, ctx->K));
   TRY(make_f32(ctx, ctx->K, true));
   TRY(pack_fused(ctx, ctx->K));
+  if (ctx->k > 0) {
+    DevLevel& K = ctx->K;
+    const size_t n0r = (size_t)std::max(K.nc, 1) * 6 * K.nK;
+    TRY(dalloc(ctx, &K.y0K, (size_t)std::max(K.nc, 1) * 6));
+    if (vc_f32(ctx)) {
+      TRY(dalloc(ctx, &K.S0_32, n0r));
+      launch_pack_mode0_rows<float>(ctx->st, K.nc, K.m, K.S, K.S0_32);
+    } else {
+      TRY(dalloc(ctx, &K.S0, n0r));
+      launch_pack_mode0_rows<double>(ctx->st, K.nc, K.m, K.S, K.S0);
+    }
+    HIPC(hipGetLastError());
+  }
   ctx->hostB.assign(ctx->J, {});
   std::vector<std::vector<double>> nu;
   level_viscosities(ctx->lv, ctx->nu_fine, nu);
@@ -2240,7 +2264,11 @@ hdgmg_status hdgmg_assemble(hdgmg_ctx* ctx) {
       const DevLevel& K = ctx->K;
       double sw = 0.0;
       for (int c = 0; c < (int)K.colour_ptr.size() - 1; ++c) sw += phase_bytes(ctx, K, -1, c);
-      const double res = K.fast ? K.bytes_cell_vc + K.bytes_sum : ctx->apply_bytes * (K.f32 ? 0.5 : 1.0);
+      // the residual: its mode-0 rows (the six rows' words, x once per cell
+      // facet, the rows' products written and read, b's and g0's entries)
+      const double res = o.additive ? 0.0
+                                    : (vc_f32(ctx) ? 4.0 : 8.0) * K.nc * 6.0 * K.nK +
+                                          8.0 * (K.nc * (double)K.nK + 3.0 * K.nc * 6.0 + 2.0 * 2.0 * K.nint);
       const double first = K.fused ? K.bytes_fused_vc[0] - K.bytes_relax_vc[0] : K.fast ? K.bytes_cell_vc : 0.0;
       v += 2.0 * o.m_relax * sw - first + res;  // sweeps, residual
       v += 2.0 * K.ndof * 8.0;                                                 // the mode-0 transfers
@@ -2284,8 +2312,11 @@ hdgmg_status hdgmg_assemble(hdgmg_ctx* ctx) {
     const double wl = o.vcycle_precision == 0 ? 8.0 : 4.0;
     double vc = 0.0;
     if (ctx->k > 0) {
+      // the order-k residual enters MG_hp only through its mode-0 rows
       const Level& LK = ctx->lv[ctx->J - 1];
-      vc += 2.0 * o.m_relax * sweep_c(LK, ctx->k + 1, wk) + res_c(LK, ctx->k + 1, wk);
+      const double w0 = vc_f32(ctx) ? 4.0 : 8.0;
+      vc += 2.0 * o.m_relax * sweep_c(LK, ctx->k + 1, wk) +
+            (o.additive ? 0.0 : LK.nc * 6.0 * 6.0 * (ctx->k + 1) * w0 + 3.0 * 8.0 * 2.0 * LK.nint);
     }
     double vis = 1.0, ml = o.m_smooth;
     for (int l = ctx->J - 1; l >= 1; --l) {
