@@ -819,14 +819,17 @@ __global__ void k_copy(long n, const double* __restrict__ x, double* __restrict_
   if (t < n) y[t] = x[t];
 }
 
+// Sum over the workgroup (a multiple of 64 threads), returned to every
+// thread: each wavefront sums by shuffles, then the wavefronts' sums meet in
+// LDS (sh: one word per wavefront, reusable after the return).
 __device__ inline double block_sum(double v, double* sh) {
-  sh[threadIdx.x] = v;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  const int nw = blockDim.x >> 6;
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-    __syncthreads();
-  }
-  double r = sh[0];
+  double r = 0.0;
+  for (int i = 0; i < nw; ++i) r += sh[i];
   __syncthreads();
   return r;
 }
@@ -834,7 +837,7 @@ __device__ inline double block_sum(double v, double* sh) {
 // block partials of sum_{K,q} w_q |K| |a - b|^2 over [nc][nq][2] fields (b may be null)
 __global__ void k_wdiff2(QuadTables Q, const double* __restrict__ X, const int* __restrict__ cells, int nc,
                          const double* __restrict__ a, const double* __restrict__ b, double* part) {
-  __shared__ double sh[TPB];
+  __shared__ double sh[TPB / 64];
   double s = 0.0;
   for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < (long)nc * Q.nq; t += (long)gridDim.x * blockDim.x) {
     const long c = t / Q.nq;
@@ -867,7 +870,7 @@ __global__ void k_dirichlet_const(int nb, int m, const double* __restrict__ tb, 
 }
 
 __global__ void k_dot(long n, const double* __restrict__ x, const double* __restrict__ y, double* part) {
-  __shared__ double sh[TPB];
+  __shared__ double sh[TPB / 64];
   double s = 0.0;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
     s += x[i] * y[i];
@@ -877,7 +880,7 @@ __global__ void k_dot(long n, const double* __restrict__ x, const double* __rest
 
 __global__ void k_dot2(long n, const double* __restrict__ z, const double* __restrict__ r,
                        const double* __restrict__ r2, double* part) {
-  __shared__ double sh[TPB];
+  __shared__ double sh[TPB / 64];
   double s1 = 0.0, s2 = 0.0;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
     s1 += z[i] * r[i];
@@ -891,17 +894,26 @@ __global__ void k_dot2(long n, const double* __restrict__ z, const double* __res
   }
 }
 
-// part[i * gridDim.x + block] = partial sums of V_i . w, i < nv (V_i = V + i * ld)
+// part[i * gridDim.x + block] = partial sums of V_i . w, i < nv (V_i = V + i * ld);
+// eight basis vectors per pass, so that w is read once per eight
 __global__ void k_mdot(long n, int nv, const double* __restrict__ V, long ld, const double* __restrict__ w,
                        double* part) {
-  __shared__ double sh[TPB];
-  for (int i = 0; i < nv; ++i) {
-    const double* v = V + (long)i * ld;
-    double s = 0.0;
-    for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x)
-      s += v[t] * w[t];
-    double r = block_sum(s, sh);
-    if (threadIdx.x == 0) part[(long)i * gridDim.x + blockIdx.x] = r;
+  __shared__ double sh[TPB / 64];
+  for (int i0 = 0; i0 < nv; i0 += 8) {
+    const int g = min(8, nv - i0);
+    double s[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) s[i] = 0.0;
+    for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
+      const double wt = w[t];
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        if (i < g) s[i] += V[(long)(i0 + i) * ld + t] * wt;
+    }
+    for (int i = 0; i < g; ++i) {
+      const double r = block_sum(s[i], sh);
+      if (threadIdx.x == 0) part[(long)(i0 + i) * gridDim.x + blockIdx.x] = r;
+    }
   }
 }
 
@@ -921,7 +933,7 @@ __global__ void k_scale(long n, double a, const double* __restrict__ x, double* 
 }
 
 __global__ void k_finalize(const double* __restrict__ part, int nblocks, int nvals, double* sc, int slot0) {
-  __shared__ double sh[TPB];
+  __shared__ double sh[TPB / 64];
   for (int v = 0; v < nvals; ++v) {
     double s = 0.0;
     for (int i = threadIdx.x; i < nblocks; i += blockDim.x) s += part[(long)v * nblocks + i];
@@ -932,7 +944,7 @@ __global__ void k_finalize(const double* __restrict__ part, int nblocks, int nva
 
 __global__ void k_fcg_xr(long n, double* x, double* r, double* r_old, const double* __restrict__ p,
                          const double* __restrict__ q, const double* __restrict__ sc, double* part) {
-  __shared__ double sh[TPB];
+  __shared__ double sh[TPB / 64];
   const double alpha = sc[SC_ZR] / sc[SC_PQ];
   double s = 0.0;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
@@ -973,7 +985,7 @@ __global__ void k_uzawa_rhs(int nint, int m, const double* __restrict__ g, const
 __global__ void k_uzawa_update(int nc, int m, const int* __restrict__ cell_dofs, const double* __restrict__ cdiv,
                                const double* __restrict__ area, const double* __restrict__ lam,
                                double eps_inv, const double* __restrict__ cflux, double* p0, double* part) {
-  __shared__ double sh[TPB];
+  __shared__ double sh[TPB / 64];
   double s1 = 0.0, s2 = 0.0;
   for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += (long)gridDim.x * blockDim.x) {
     double dv = cflux ? cflux[c] : 0.0;  // prescribed boundary flux
