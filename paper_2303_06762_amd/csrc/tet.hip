@@ -901,11 +901,14 @@ __global__ void __launch_bounds__(BS) k_patch_gs3(Level3View<TS> L, const int* _
                                                   const int* __restrict__ pc, const long* __restrict__ poff,
                                                   const TP* __restrict__ pinv, int p0, double* x,
                                                   const double* __restrict__ b) {
+  // the wavefront form serves the lowest-order levels (mF = 1) only: LDS
+  // sized for them (2 KB instead of 20 KB) lets a CU hold many more
+  constexpr int MFL = BS == 64 ? 1 : MF3MAX;
   __shared__ int slot[PMAX_CELLS][4];
   __shared__ int cellid[PMAX_CELLS];
-  __shared__ double xs[PMAX_CELLS][12 * MF3MAX];
-  __shared__ double res[PMAX_FACES * 3 * MF3MAX];
-  __shared__ double side[2][PMAX_FACES * 3 * MF3MAX];
+  __shared__ double xs[PMAX_CELLS][12 * MFL];
+  __shared__ double res[PMAX_FACES * 3 * MFL];
+  __shared__ double side[2][PMAX_FACES * 3 * MFL];
   const int p = p0 + blockIdx.x, tid = threadIdx.x;
   const int f0 = pf_ptr[p], nf = pf_ptr[p + 1] - f0, c0 = pc_ptr[p], ncl = pc_ptr[p + 1] - c0;
   const int m3 = 3 * L.mF, ns = nf * m3, nK = L.nK;
