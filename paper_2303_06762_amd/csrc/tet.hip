@@ -895,15 +895,16 @@ __global__ void __launch_bounds__(NT) k_patch_inverse3(Level3View<double> L, con
 // patch faces, S_K read along columns (symmetric blocks), eight loads in
 // flight per thread; each face's two cells write their contributions to
 // separate LDS slots, so the residual is b - side0 - side1.
-template <typename TS, typename TP, int BS>
+template <typename TS, typename TP, int BS, int MFC>
 __global__ void __launch_bounds__(BS) k_patch_gs3(Level3View<TS> L, const int* __restrict__ pf_ptr,
                                                   const int* __restrict__ pf, const int* __restrict__ pc_ptr,
                                                   const int* __restrict__ pc, const long* __restrict__ poff,
                                                   const TP* __restrict__ pinv, int p0, double* x,
                                                   const double* __restrict__ b) {
-  // the wavefront form serves the lowest-order levels (mF = 1) only: LDS
-  // sized for them (2 KB instead of 20 KB) lets a CU hold many more
-  constexpr int MFL = BS == 64 ? 1 : MF3MAX;
+  // LDS sized for at most MFC face modes (the launch picks the smallest
+  // instance that fits the level): at lowest order 2 KB instead of 20 KB, so
+  // that a CU holds many more of these latency-bound wavefronts
+  constexpr int MFL = MFC;
   __shared__ int slot[PMAX_CELLS][4];
   __shared__ int cellid[PMAX_CELLS];
   __shared__ double xs[PMAX_CELLS][12 * MFL];
@@ -1136,13 +1137,20 @@ void launch_patch_gs3(hipStream_t st, Level3View<TS> L, const int* pf_ptr, const
                       const int* pc, const long* poff, const TP* pinv, int p0, int p1, double* x,
                       const double* b) {
   if (p1 <= p0) return;
-  // lowest-order patches (at most 36 unknowns): a wavefront each
+  // lowest-order patches (at most 36 unknowns): a wavefront each; order k:
+  // a workgroup of NT with LDS for the level's face modes
+#define GS3(B, M)                                                                                          \
+  hipLaunchKernelGGL((k_patch_gs3<TS, TP, B, M>), dim3(p1 - p0), dim3(B), 0, st, L, pf_ptr, pf, pc_ptr, pc, poff, \
+                     pinv, p0, x, b)
   if (L.mF == 1)
-    hipLaunchKernelGGL((k_patch_gs3<TS, TP, 64>), dim3(p1 - p0), dim3(64), 0, st, L, pf_ptr, pf, pc_ptr, pc, poff,
-                       pinv, p0, x, b);
+    GS3(64, 1);
+  else if (L.mF <= 3)
+    GS3(NT, 3);
+  else if (L.mF <= 6)
+    GS3(NT, 6);
   else
-    hipLaunchKernelGGL((k_patch_gs3<TS, TP, NT>), dim3(p1 - p0), dim3(NT), 0, st, L, pf_ptr, pf, pc_ptr, pc, poff,
-                       pinv, p0, x, b);
+    GS3(NT, MF3MAX);
+#undef GS3
 }
 template void launch_patch_gs3<double, double>(hipStream_t, Level3View<double>, const int*, const int*, const int*,
                                                const int*, const long*, const double*, int, int, double*,
