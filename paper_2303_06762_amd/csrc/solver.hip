@@ -1335,31 +1335,25 @@ hdgmg_status level_records(hdgmg_ctx* ctx, int l, int max_items, LevelRecords& R
   R.nsm = nsm;
   R.cb.assign(1, 0);
   R.bitem.assign(1, 0);
-  // patch inverses (host FP64), patches split over threads; the unknown ->
-  // patch-row map of a thread marks the current patch's unknowns
+  // the patch inverses as the assembly computed them on the device
+  // (patch_inverses: column-major per patch, in the level's patch order,
+  // singular blocks already rejected there), copied back once
   const int npatch = L.colour_ptr[L.ncol];
-  std::vector<std::vector<double>> invs(npatch);
-  std::vector<char> pok(npatch, 1);
-  {
-    const int nth = npatch >= 1024 ? (int)std::min(16u, std::max(1u, std::thread::hardware_concurrency())) : 1;
-    std::vector<std::thread> th;
-    for (int w = 0; w < nth; ++w)
-      th.emplace_back([&, w] {
-        std::vector<int> slot(n, -1);
-        for (int p = w; p < npatch; p += nth) {
-          const int f0 = L.patch_facet_ptr[p], nfp = L.patch_facet_ptr[p + 1] - f0, ns = 2 * nfp;
-          for (int a = 0; a < ns; ++a) slot[2 * L.patch_facets[f0 + a / 2] + a % 2] = a;
-          std::vector<double> Ass((size_t)ns * ns, 0.0);
-          for (int i = 0; i < ns; ++i) {
-            const int di = 2 * L.patch_facets[f0 + i / 2] + i % 2;
-            for (int q = A.rp[di]; q < A.rp[di + 1]; ++q)
-              if (slot[A.ci[q]] >= 0) Ass[(size_t)i * ns + slot[A.ci[q]]] = A.v[q];
-          }
-          for (int a = 0; a < ns; ++a) slot[2 * L.patch_facets[f0 + a / 2] + a % 2] = -1;
-          pok[p] = ctx->opts.oseen ? invert_general(Ass, ns, invs[p]) : invert_spd(Ass, ns, invs[p]);
-        }
-      });
-    for (auto& t : th) t.join();
+  const DevLevel& DL = ctx->cr[l];
+  std::vector<long> poff(npatch + 1, 0);
+  for (int p = 0; p < npatch; ++p) {
+    const long ns = 2L * (L.patch_facet_ptr[p + 1] - L.patch_facet_ptr[p]);
+    poff[p + 1] = poff[p] + ns * ns;
+  }
+  if (poff[npatch] != DL.pinv_len) {
+    ctx->err = "record construction: patch inverse layout mismatch";
+    return HDGMG_EMESH;
+  }
+  std::vector<double> pinv_h((size_t)std::max<long>(DL.pinv_len, 1));
+  if (DL.pinv_len > 0) {
+    HIPC(hipMemcpyAsync(pinv_h.data(), DL.pinv, (size_t)DL.pinv_len * sizeof(double), hipMemcpyDeviceToHost,
+                        ctx->st));
+    HIPC(hipStreamSynchronize(ctx->st));
   }
   std::vector<int> idof, iloc;
   std::vector<double> irow;  // [item][nsm]
@@ -1376,11 +1370,7 @@ hdgmg_status level_records(hdgmg_ctx* ctx, int l, int max_items, LevelRecords& R
       std::vector<int> dofs(ns);
       for (int a = 0; a < nfp; ++a)
         for (int comp = 0; comp < 2; ++comp) dofs[2 * a + comp] = 2 * L.patch_facets[f0 + a] + comp;
-      if (!pok[p]) {
-        ctx->err = "singular patch block on a lowest-order level";
-        return HDGMG_ENONFINITE;
-      }
-      const std::vector<double>& inv = invs[p];
+      const double* inv = pinv_h.data() + poff[p];
       if ((int)idof.size() - R.bitem.back() + ns > max_items) {
         while (pad && (int)idof.size() - R.bitem.back() < max_items) {
           idof.push_back(-1);
