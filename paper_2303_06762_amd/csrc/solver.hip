@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -1404,7 +1405,10 @@ hdgmg_status level_records(hdgmg_ctx* ctx, int l, int max_items, LevelRecords& R
   const int nvg = (COARSE_NNZ + G - 1) / G, nag = (std::max(nsm, 1) + G - 1) / G;
   R.val.assign((size_t)nvg * G * nit, 0.0);
   R.ainv.assign((size_t)nag * G * nit, 0.0);
-  for (int t = 0; t < nit; ++t) {
+  // items are independent: contiguous ranges of them on host threads
+  std::atomic<bool> bad_pairs{false};
+  auto fill = [&](int t_begin, int t_end) {
+  for (int t = t_begin; t < t_end; ++t) {
     if (idof[t] < 0) {  // padding: row marker REC_PAD, unknown 0, zero values
       if (wide)
         R.meta[(size_t)t * 8 + 1] = REC_PAD;
@@ -1432,8 +1436,8 @@ hdgmg_status level_records(hdgmg_ctx* ctx, int l, int max_items, LevelRecords& R
       const double v0 = val(2 * q), v1 = val(2 * q + 1);
       const bool padded = c0 == 0 && c1 == 0 && v0 == 0.0 && v1 == 0.0;
       if (!padded && (c0 % 2 != 0 || c1 != c0 + 1)) {
-        ctx->err = "lowest-order row whose columns are not facet pairs";
-        return HDGMG_EMESH;
+        bad_pairs = true;
+        return;
       }
       if (wide)
         R.meta[(size_t)t * 8 + 2 + q] = (unsigned)(padded ? 0 : c0 / 2);
@@ -1441,6 +1445,18 @@ hdgmg_status level_records(hdgmg_ctx* ctx, int l, int max_items, LevelRecords& R
         R.meta[(size_t)t * 4 + 1 + q / 2] |= (unsigned)(padded ? 0 : c0 / 2) << (16 * (q % 2));
     }
     for (int j = 0; j < nsm; ++j) R.ainv[((size_t)(j / G) * nit + t) * G + j % G] = irow[(size_t)t * nsm + j];
+  }
+  };
+  {
+    const int nth = nit >= 16384 ? (int)std::min(16u, std::max(1u, std::thread::hardware_concurrency())) : 1;
+    const int chunk = (nit + nth - 1) / nth;
+    std::vector<std::thread> th;
+    for (int w = 0; w < nth; ++w) th.emplace_back(fill, std::min(nit, w * chunk), std::min(nit, (w + 1) * chunk));
+    for (auto& t : th) t.join();
+  }
+  if (bad_pairs) {
+    ctx->err = "lowest-order row whose columns are not facet pairs";
+    return HDGMG_EMESH;
   }
   for (int c = L.ncol - 1; c >= 0; --c)
     for (int bb = R.cb[c]; bb < R.cb[c + 1]; ++bb) R.bwd.push_back(bb);
