@@ -35,6 +35,9 @@ struct DevLev3 {
   std::vector<int> colour_ptr, hns;
   int *pf_ptr = nullptr, *pf = nullptr, *pc_ptr = nullptr, *pc = nullptr;
   long* poff = nullptr;
+  // lowest-order edge patches: per patch cell the cell's four face numbers
+  // and (cell, packed patch faces / slots / sides), in patch-cell order
+  int *pdofs = nullptr, *pcode = nullptr;
   long pinv_len = 0;
   double* pinv = nullptr;
   float* pinv32 = nullptr;
@@ -520,6 +523,42 @@ hdgmg_status upload_level(Ctx3* c, const Level3& L, int mF, DevLev3& D) {
   TRY3(upload(c, &D.pf, L.pf));
   TRY3(upload(c, &D.pc_ptr, L.pc_ptr));
   TRY3(upload(c, &D.pc, L.pc));
+  if (mF == 1 && !D.vertex) {
+    // records of the lowest-order colour phase (else the general kernel)
+    const size_t npc = L.pc.size();
+    std::vector<int> pdofs(4 * npc), pcode(2 * npc);
+    bool ok = true;
+    for (int p = 0; p < (int)L.pc_ptr.size() - 1 && ok; ++p) {
+      const int f0 = L.pf_ptr[p], nf = L.pf_ptr[p + 1] - f0;
+      if (nf < 1 || nf > 12 || L.pc_ptr[p + 1] - L.pc_ptr[p] > 12) ok = false;
+      for (int j = L.pc_ptr[p]; j < L.pc_ptr[p + 1] && ok; ++j) {
+        const int K = L.pc[j];
+        int code = 15 << 4 | 15 << 8, cnt = 0;
+        for (int i = 0; i < 4; ++i) {
+          const int dof = L.cell_dofs[4 * K + i];
+          pdofs[4 * (size_t)j + i] = dof;
+          int sl = -1;
+          for (int q = 0; q < nf; ++q)
+            if (dof >= 0 && L.pf[f0 + q] == dof) sl = q;
+          if (sl < 0) continue;
+          if (cnt == 2) {
+            ok = false;
+            break;
+          }
+          const int sd = fcell[2 * (size_t)dof] == K ? 0 : 1;
+          code = (code & ~(3 << (2 * cnt)) & ~(15 << (4 + 4 * cnt))) | i << (2 * cnt) | sl << (4 + 4 * cnt) |
+                 sd << (12 + cnt);
+          ++cnt;
+        }
+        pcode[2 * (size_t)j] = K;
+        pcode[2 * (size_t)j + 1] = code;
+      }
+    }
+    if (ok && npc > 0) {
+      TRY3(upload(c, &D.pdofs, pdofs));
+      TRY3(upload(c, &D.pcode, pcode));
+    }
+  }
   D.hpoff.assign(D.np + 1, 0);
   D.hns.assign(D.np, 0);
   D.ns_max = 0;
@@ -686,7 +725,16 @@ void sweep(Ctx3* c, DevLev3& D, double* x, const double* b, bool forward, int cl
     const int col = forward ? ci : D.ncol - 1 - ci;
     const int p0 = D.colour_ptr[col], p1 = D.colour_ptr[col + 1];
     const int t = kt_begin(c, cls);
-    if (f32(c) && pinv64(c, D))
+    if (D.pcode && f32(c) && pinv64(c, D))
+      launch_patch_gs3_lo<float, double>(c->st, view32(c, D), D.pf_ptr, D.pf, D.pc_ptr, D.pdofs, D.pcode, D.poff,
+                                         D.pinv, p0, p1, x, b);
+    else if (D.pcode && f32(c))
+      launch_patch_gs3_lo<float, float>(c->st, view32(c, D), D.pf_ptr, D.pf, D.pc_ptr, D.pdofs, D.pcode, D.poff,
+                                        D.pinv32, p0, p1, x, b);
+    else if (D.pcode)
+      launch_patch_gs3_lo<double, double>(c->st, view<double>(D, D.S), D.pf_ptr, D.pf, D.pc_ptr, D.pdofs, D.pcode,
+                                          D.poff, D.pinv, p0, p1, x, b);
+    else if (f32(c) && pinv64(c, D))
       launch_patch_gs3<float, double>(c->st, view32(c, D), D.pf_ptr, D.pf, D.pc_ptr, D.pc, D.poff, D.pinv, p0,
                                       p1, x, b);
     else if (f32(c))

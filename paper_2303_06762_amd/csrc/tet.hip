@@ -991,6 +991,129 @@ __global__ void __launch_bounds__(BS) k_patch_gs3(Level3View<TS> L, const int* _
   }
 }
 
+// The same colour phase at lowest order (one mode per face component: 3
+// unknowns per face, 12 per cell), a wavefront per patch.  Records built at
+// set-up give, per patch cell, the cell's four face numbers and the cell
+// with its two patch faces (local index, slot in the patch, side), so every
+// load depends on at most two earlier ones (the patch's ranges, then its
+// records and face list), and each lane issues its twelve row entries,
+// twelve cell values and its row of the patch inverse together.  The
+// arithmetic, and its order, are those of k_patch_gs3 at one face mode.
+// One item of the lowest-order phase below: row rr of the patch face
+// `which` of patch cell (dv, cc), S_K row times x_K (+ the AL term when it is
+// kept apart), into side[sd][slot].
+template <typename TS>
+__device__ __forceinline__ void gs3_lo_item(const Level3View<TS>& L, bool live, int which, int rr, int4 dv,
+                                            int2 cc, const double* x, double (*side)[PMAX_FACES * 3]) {
+  const int cell = cc.x, i = (cc.y >> (2 * which)) & 3, s = (cc.y >> (4 + 4 * which)) & 15,
+            sd = (cc.y >> (12 + which)) & 1;
+  const TS* Sc = L.S + (long)cell * 144 + i * 36 + rr;
+  double v[12], xc[12];
+#pragma unroll
+  for (int u = 0; u < 12; ++u) v[u] = (double)Sc[u * 3];
+  const int d[4] = {dv.x, dv.y, dv.z, dv.w};
+#pragma unroll
+  for (int f = 0; f < 4; ++f)
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const double t = x[(long)max(d[f], 0) * 3 + r];
+      xc[3 * f + r] = d[f] >= 0 ? t : 0.0;
+    }
+  double cd[4] = {0.0, 0.0, 0.0, 0.0}, vK = 1.0;
+  if (L.al > 0.0) {
+#pragma unroll
+    for (int f = 0; f < 4; ++f) cd[f] = L.cdiv[4 * cell + f];
+    vK = L.vol[cell];
+  }
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  a0 += v[0] * xc[0] + v[4] * xc[4];
+  a1 += v[1] * xc[1] + v[5] * xc[5];
+  a2 += v[2] * xc[2] + v[6] * xc[6];
+  a3 += v[3] * xc[3] + v[7] * xc[7];
+#pragma unroll
+  for (int u = 8; u < 12; ++u) a0 += v[u] * xc[u];
+  double acc = (a0 + a1) + (a2 + a3);
+  if (L.al > 0.0 && rr == 0) {
+    double dx = 0.0;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) dx += cd[f] * xc[3 * f];
+    const double di = i == 0 ? cd[0] : i == 1 ? cd[1] : i == 2 ? cd[2] : cd[3];
+    acc += L.al / vK * di * dx;
+  }
+  if (live && s < 15) side[sd][s * 3 + rr] = acc;
+}
+
+// The same colour phase at lowest order (one mode per face component: 3
+// unknowns per face, 12 per cell), a wavefront per patch.  Records built at
+// set-up give, per patch cell, the cell's four face numbers and the cell
+// with its two patch faces (local index, slot in the patch, side), so every
+// load depends on at most two earlier ones (the patch's ranges, then its
+// records and face list), and each lane issues its twelve row entries,
+// twelve cell values and its row of the patch inverse together.  The
+// arithmetic, and its order, are those of k_patch_gs3 at one face mode.
+template <typename TS, typename TP>
+__global__ void __launch_bounds__(64) k_patch_gs3_lo(Level3View<TS> L, const int* __restrict__ pf_ptr,
+                                                     const int* __restrict__ pf, const int* __restrict__ pc_ptr,
+                                                     const int4* __restrict__ pdofs, const int2* __restrict__ pcode,
+                                                     const long* __restrict__ poff, const TP* __restrict__ pinv,
+                                                     int p0, double* x, const double* __restrict__ b) {
+  __shared__ double res[PMAX_FACES * 3];
+  __shared__ double side[2][PMAX_FACES * 3];
+  const int p = p0 + blockIdx.x, lane = threadIdx.x;
+  // the patch's ranges and inverse offset, loaded together
+  const int f0 = pf_ptr[p], f1 = pf_ptr[p + 1], c0 = pc_ptr[p], c1 = pc_ptr[p + 1];
+  const long po = poff[p];
+  const int nf = f1 - f0, ncl = c1 - c0;
+  if (nf < 1 || nf > PMAX_FACES || ncl < 1 || ncl > PMAX_CELLS) return;  // rejected on the host
+  const int ns = 3 * nf, nit = 6 * ncl;
+  // first: the face of this lane's patch unknown (lanes past ns: a copy of
+  // the last, unused) and the records of its first item
+  const int q = min(lane, ns - 1);
+  const int fq = pf[f0 + q / 3];
+  const int ciA = min(lane / 6, ncl - 1);
+  const int4 dvA = pdofs[c0 + ciA];
+  const int2 ccA = pcode[c0 + ciA];
+  // then its row of the patch inverse, every column index clamped into the
+  // row: the loads carry no branch, so that waiting for any later load does
+  // not wait for these (columns past ns are read again and not used)
+  const TP* Ai = pinv + po;
+  double av[3 * PMAX_FACES];
+#pragma unroll
+  for (int j = 0; j < 3 * PMAX_FACES; ++j) av[j] = (double)Ai[(long)min(j, ns - 1) * ns + q];
+  const long xq = (long)fq * 3 + q % 3;
+  const double bq = b[xq];
+  if (lane < ns) {
+    side[0][lane] = 0.0;
+    side[1][lane] = 0.0;
+  }
+  __syncthreads();
+  gs3_lo_item(L, lane < nit, (lane / 3) & 1, lane % 3, dvA, ccA, x, side);
+  if (nit > 64) {  // more than ten cells around the edge
+    const int it = 64 + lane;
+    const int ci = min(it / 6, ncl - 1);
+    gs3_lo_item(L, it < nit, (it / 3) & 1, it % 3, pdofs[c0 + ci], pcode[c0 + ci], x, side);
+  }
+  __syncthreads();
+  if (lane < ns) res[lane] = bq - (side[0][lane] + side[1][lane]);
+  __syncthreads();
+  if (lane < ns) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    const int n4 = ns / 4 * 4;
+#pragma unroll
+    for (int j = 0; j < 3 * PMAX_FACES; j += 4)
+      if (j < n4) {
+        a0 += av[j] * res[j];
+        a1 += av[j + 1] * res[j + 1];
+        a2 += av[j + 2] * res[j + 2];
+        a3 += av[j + 3] * res[j + 3];
+      }
+#pragma unroll
+    for (int j = 0; j < 3 * PMAX_FACES; ++j)
+      if (j >= n4 && j < ns) a0 += av[j] * res[j];
+    x[xq] += (a0 + a1) + (a2 + a3);
+  }
+}
+
 __global__ void k_mode0_extract3(int n, int mF, const double* __restrict__ r, double* __restrict__ g0,
                                  double* __restrict__ zero_out) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1161,6 +1284,25 @@ template void launch_patch_gs3<float, float>(hipStream_t, Level3View<float>, con
 template void launch_patch_gs3<float, double>(hipStream_t, Level3View<float>, const int*, const int*, const int*,
                                               const int*, const long*, const double*, int, int, double*,
                                               const double*);
+
+template <typename TS, typename TP>
+void launch_patch_gs3_lo(hipStream_t st, Level3View<TS> L, const int* pf_ptr, const int* pf, const int* pc_ptr,
+                         const int* pdofs, const int* pcode, const long* poff, const TP* pinv, int p0, int p1,
+                         double* x, const double* b) {
+  if (p1 <= p0) return;
+  hipLaunchKernelGGL((k_patch_gs3_lo<TS, TP>), dim3(p1 - p0), dim3(64), 0, st, L, pf_ptr, pf, pc_ptr,
+                     reinterpret_cast<const int4*>(pdofs), reinterpret_cast<const int2*>(pcode), poff, pinv, p0, x,
+                     b);
+}
+template void launch_patch_gs3_lo<double, double>(hipStream_t, Level3View<double>, const int*, const int*,
+                                                  const int*, const int*, const int*, const long*, const double*,
+                                                  int, int, double*, const double*);
+template void launch_patch_gs3_lo<float, float>(hipStream_t, Level3View<float>, const int*, const int*, const int*,
+                                                const int*, const int*, const long*, const float*, int, int,
+                                                double*, const double*);
+template void launch_patch_gs3_lo<float, double>(hipStream_t, Level3View<float>, const int*, const int*,
+                                                 const int*, const int*, const int*, const long*, const double*,
+                                                 int, int, double*, const double*);
 
 void launch_mode0_extract3(hipStream_t st, int nint, int mF, const double* r, double* g0, double* zero_out) {
   const int n = 3 * nint;

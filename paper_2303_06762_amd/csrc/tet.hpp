@@ -150,6 +150,17 @@ template <typename TS, typename TP>
 void launch_patch_gs3(hipStream_t st, Level3View<TS> L, const int* pf_ptr, const int* pf, const int* pc_ptr,
                       const int* pc, const long* poff, const TP* pinv, int p0, int p1, double* x,
                       const double* b);
+// The same at lowest order (mF = 1), a wavefront per patch, from per patch
+// cell records in patch-cell order: pdofs [4] = the cell's four interior
+// face numbers (or -1), pcode [2] = the cell and a code packing the local
+// indices i0, i1 (2 bits each, bits 0-3) of its patch faces, their slots in
+// the patch face list (4 bits each, bits 4-11; 15 = none) and their sides
+// (the cell is fcell[2f + side]; bits 12 and 13).  Device arrays, 16- and
+// 8-byte aligned.
+template <typename TS, typename TP>
+void launch_patch_gs3_lo(hipStream_t st, Level3View<TS> L, const int* pf_ptr, const int* pf, const int* pc_ptr,
+                         const int* pdofs, const int* pcode, const long* poff, const TP* pinv, int p0, int p1,
+                         double* x, const double* b);
 // Lowest-order part of an order-k skeleton vector (mode 0 of each face
 // component) and its injection.
 void launch_mode0_extract3(hipStream_t st, int nint, int mF, const double* r, double* g0, double* zero_out);
