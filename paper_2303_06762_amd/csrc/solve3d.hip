@@ -45,6 +45,9 @@ struct DevLev3 {
   // words each colour phase reads: cell-block entries, patch-inverse
   // entries, and vector words (FP64)
   std::vector<double> phase_S, phase_P, phase_V;
+  // vector words of a phase from x = 0 (b read, x read and written on the
+  // patch faces; no cell blocks or cell vectors)
+  std::vector<double> phase_V0;
   double *u = nullptr, *g = nullptr, *r = nullptr, *yK = nullptr;
   // order-k level: the twelve mode-0 rows of every cell block ([nK][12][nc],
   // in the V-cycle's storage, FP32 without the AL term) and their products,
@@ -581,6 +584,7 @@ hdgmg_status upload_level(Ctx3* c, const Level3& L, int mF, DevLev3& D) {
   D.phase_S.assign(D.ncol, 0.0);
   D.phase_P.assign(D.ncol, 0.0);
   D.phase_V.assign(D.ncol, 0.0);
+  D.phase_V0.assign(D.ncol, 0.0);
   for (int col = 0; col < D.ncol; ++col) {
     if (D.vertex) {
       // vertex patches: a full residual per colour, then the patch inverses
@@ -591,6 +595,7 @@ hdgmg_status upload_level(Ctx3* c, const Level3& L, int mF, DevLev3& D) {
       const double ns = (double)(L.pf_ptr[p + 1] - L.pf_ptr[p]) * 3 * mF;
       const double ncl = L.pc_ptr[p + 1] - L.pc_ptr[p];
       D.phase_P[col] += ns * ns;
+      D.phase_V0[col] += 3.0 * ns;
       if (D.vertex) {
         D.phase_V[col] += 3.0 * ns;
       } else {
@@ -679,6 +684,11 @@ double phase_bytes(const Ctx3* c, const DevLev3& D, int col) {
   const double bs = f32(c) ? 4.0 : 8.0, bp = f32(c) && !pinv64(c, D) ? 4.0 : 8.0;
   return D.phase_S[col] * bs + D.phase_P[col] * bp + D.phase_V[col] * 8.0;
 }
+// the same for an edge-patch phase from x = 0
+double phase_bytes_zero(const Ctx3* c, const DevLev3& D, int col) {
+  const double bp = f32(c) && !pinv64(c, D) ? 4.0 : 8.0;
+  return D.phase_P[col] * bp + D.phase_V0[col] * 8.0;
+}
 
 // Damped block Jacobi sweep (eq. bjac): r = b - A x once, then every
 // colour's patches add A_ss^-1 r_s / (number of colours)
@@ -698,7 +708,9 @@ void jacobi_sweep(Ctx3* c, DevLev3& D, double* x, const double* b, int cls) {
   }
 }
 
-void sweep(Ctx3* c, DevLev3& D, double* x, const double* b, bool forward, int cls) {
+// x_zero: x = 0 at entry, so the first colour phase of an edge-patch
+// Gauss-Seidel sweep forms its patch residuals from b alone
+void sweep(Ctx3* c, DevLev3& D, double* x, const double* b, bool forward, int cls, bool x_zero = false) {
   if (c->opts.smoother == 1) {
     jacobi_sweep(c, D, x, b, cls);
     return;
@@ -724,26 +736,27 @@ void sweep(Ctx3* c, DevLev3& D, double* x, const double* b, bool forward, int cl
   for (int ci = 0; ci < D.ncol; ++ci) {
     const int col = forward ? ci : D.ncol - 1 - ci;
     const int p0 = D.colour_ptr[col], p1 = D.colour_ptr[col + 1];
+    const bool fz = x_zero && ci == 0;
     const int t = kt_begin(c, cls);
     if (D.pcode && f32(c) && pinv64(c, D))
       launch_patch_gs3_lo<float, double>(c->st, view32(c, D), D.pf_ptr, D.pf, D.pc_ptr, D.pdofs, D.pcode, D.poff,
-                                         D.pinv, p0, p1, x, b);
+                                         D.pinv, p0, p1, x, b, fz);
     else if (D.pcode && f32(c))
       launch_patch_gs3_lo<float, float>(c->st, view32(c, D), D.pf_ptr, D.pf, D.pc_ptr, D.pdofs, D.pcode, D.poff,
-                                        D.pinv32, p0, p1, x, b);
+                                        D.pinv32, p0, p1, x, b, fz);
     else if (D.pcode)
       launch_patch_gs3_lo<double, double>(c->st, view<double>(D, D.S), D.pf_ptr, D.pf, D.pc_ptr, D.pdofs, D.pcode,
-                                          D.poff, D.pinv, p0, p1, x, b);
+                                          D.poff, D.pinv, p0, p1, x, b, fz);
     else if (f32(c) && pinv64(c, D))
       launch_patch_gs3<float, double>(c->st, view32(c, D), D.pf_ptr, D.pf, D.pc_ptr, D.pc, D.poff, D.pinv, p0,
-                                      p1, x, b);
+                                      p1, x, b, fz);
     else if (f32(c))
       launch_patch_gs3<float, float>(c->st, view32(c, D), D.pf_ptr, D.pf, D.pc_ptr, D.pc, D.poff, D.pinv32, p0,
-                                     p1, x, b);
+                                     p1, x, b, fz);
     else
       launch_patch_gs3<double, double>(c->st, view<double>(D, D.S), D.pf_ptr, D.pf, D.pc_ptr, D.pc, D.poff,
-                                       D.pinv, p0, p1, x, b);
-    kt_end(c, cls, t, phase_bytes(c, D, col));
+                                       D.pinv, p0, p1, x, b, fz);
+    kt_end(c, cls, t, fz ? phase_bytes_zero(c, D, col) : phase_bytes(c, D, col));
   }
 }
 
@@ -757,7 +770,8 @@ void ell(Ctx3* c, int n, int w, const int* ci, const double* v, const float* v32
 
 // Alg. 1 on lowest-order level l from the iterate in cr[l].u (zero when
 // called from MG_hp), right-hand side cr[l].g
-void mg_h(Ctx3* c, int l, int m_l) {
+// u_zero: D.u = 0 at entry (the restriction or the caller cleared it)
+void mg_h(Ctx3* c, int l, int m_l, bool u_zero) {
   DevLev3& D = c->cr[l];
   if (l == 0) {
     if (f32(c))
@@ -766,12 +780,12 @@ void mg_h(Ctx3* c, int l, int m_l) {
       launch_gemv_rows<double>(c->st, c->n0, c->ld0, c->coarse_rows, D.g, D.u);
     return;
   }
-  for (int s = 0; s < m_l; ++s) sweep(c, D, D.u, D.g, true, 2);
+  for (int s = 0; s < m_l; ++s) sweep(c, D, D.u, D.g, true, 2, u_zero && s == 0);
   level_apply(c, D, D.u, D.r, -1.0, D.g, true);
   DevTr3& T = c->tr[l];
   DevLev3& C = c->cr[l - 1];
   ell(c, T.ncoarse, T.Rw, T.Rci, T.Rv, T.Rv32, D.r, C.g, 0.0, C.u);
-  for (int n = 0; n < c->opts.cycle; ++n) mg_h(c, l - 1, c->opts.vcycle_growth * m_l);
+  for (int n = 0; n < c->opts.cycle; ++n) mg_h(c, l - 1, c->opts.vcycle_growth * m_l, n == 0);
   ell(c, T.nfine, T.Pw, T.Pci, T.Pv, T.Pv32, C.u, D.u, 1.0, nullptr);
   for (int s = 0; s < m_l; ++s) sweep(c, D, D.u, D.g, false, 2);
 }
@@ -784,25 +798,25 @@ void mg_hp(Ctx3* c, const double* r, double* z) {
   if (c->k == 0) {
     launch_copy(c->st, DJ.ndof, r, DJ.g);
     launch_fill(c->st, DJ.ndof, 0.0, DJ.u);
-    mg_h(c, c->J - 1, c->opts.m_smooth);
+    mg_h(c, c->J - 1, c->opts.m_smooth, true);
     launch_copy(c->st, DJ.ndof, DJ.u, z);
   } else if (c->opts.additive) {
     // additive counterpart: relaxation and lowest-order correction of r
     launch_fill(c->st, KL.ndof, 0.0, z);
-    for (int s = 0; s < c->opts.m_relax; ++s) sweep(c, KL, z, r, true, 0);
+    for (int s = 0; s < c->opts.m_relax; ++s) sweep(c, KL, z, r, true, 0, s == 0);
     for (int s = 0; s < c->opts.m_relax; ++s) sweep(c, KL, z, r, false, 0);
     launch_mode0_extract3(c->st, KL.nint, KL.mF, r, DJ.g, DJ.u);
-    mg_h(c, c->J - 1, c->opts.m_smooth);
+    mg_h(c, c->J - 1, c->opts.m_smooth, true);
     launch_mode0_add3(c->st, KL.nint, KL.mF, DJ.u, z);
   } else {
     launch_fill(c->st, KL.ndof, 0.0, z);
-    for (int s = 0; s < c->opts.m_relax; ++s) sweep(c, KL, z, r, true, 0);
+    for (int s = 0; s < c->opts.m_relax; ++s) sweep(c, KL, z, r, true, 0, s == 0);
     // Pi_k^0 (r - A z): only the mode-0 rows of A z
     if (f32(c))
       launch_mode0_residual3<float>(c->st, view32(c, KL), KL.S0_32, z, KL.y0K, r, DJ.g, DJ.u);
     else
       launch_mode0_residual3<double>(c->st, view<double>(KL, KL.S), KL.S0, z, KL.y0K, r, DJ.g, DJ.u);
-    mg_h(c, c->J - 1, c->opts.m_smooth);
+    mg_h(c, c->J - 1, c->opts.m_smooth, true);
     launch_mode0_add3(c->st, KL.nint, KL.mF, DJ.u, z);
     for (int s = 0; s < c->opts.m_relax; ++s) sweep(c, KL, z, r, false, 0);
   }
@@ -1247,10 +1261,16 @@ hdgmg_status d3_assemble(Ctx3* c) {
   auto res0 = [&](const DevLev3& D) {
     return b * D.nc * 12.0 * D.nK + 8.0 * (D.nc * (double)D.nK + 3.0 * D.nc * 12.0 + 3.0 * 3.0 * D.nint);
   };
-  if (c->k > 0) vb += 2.0 * c->opts.m_relax * level_sweep(c->K) + (c->opts.additive ? 0.0 : res0(c->K));
+  // the first edge-patch Gauss-Seidel phase of a level starts from zero
+  auto zero_saving = [&](const DevLev3& D) {
+    if (D.vertex || c->opts.smoother == 1 || D.ncol == 0) return 0.0;
+    return phase_bytes(c, D, 0) - phase_bytes_zero(c, D, 0);
+  };
+  if (c->k > 0)
+    vb += 2.0 * c->opts.m_relax * level_sweep(c->K) + (c->opts.additive ? 0.0 : res0(c->K)) - zero_saving(c->K);
   int m = c->opts.m_smooth;
   for (int l = c->J - 1; l >= 1; --l) {
-    vb += 2.0 * m * level_sweep(c->cr[l]) + level_res(c->cr[l]);
+    vb += 2.0 * m * level_sweep(c->cr[l]) + level_res(c->cr[l]) - zero_saving(c->cr[l]);
     m *= c->opts.vcycle_growth;
   }
   vb += tr_bytes * b / 8.0 + b * (double)c->n0 * c->n0;

@@ -900,7 +900,9 @@ __global__ void __launch_bounds__(BS) k_patch_gs3(Level3View<TS> L, const int* _
                                                   const int* __restrict__ pf, const int* __restrict__ pc_ptr,
                                                   const int* __restrict__ pc, const long* __restrict__ poff,
                                                   const TP* __restrict__ pinv, int p0, double* x,
-                                                  const double* __restrict__ b) {
+                                                  const double* __restrict__ b, int from_zero) {
+  // from_zero: x is zero on every face the patches see, so the patch
+  // residual is b_s and the cell blocks are not read.
   // LDS sized for at most MFC face modes (the launch picks the smallest
   // instance that fits the level): at lowest order 2 KB instead of 20 KB, so
   // that a CU holds many more of these latency-bound wavefronts
@@ -914,7 +916,8 @@ __global__ void __launch_bounds__(BS) k_patch_gs3(Level3View<TS> L, const int* _
   const int f0 = pf_ptr[p], nf = pf_ptr[p + 1] - f0, c0 = pc_ptr[p], ncl = pc_ptr[p + 1] - c0;
   const int m3 = 3 * L.mF, ns = nf * m3, nK = L.nK;
   if (nf > PMAX_FACES || ncl > PMAX_CELLS) return;  // rejected on the host
-  for (int e = tid; e < ncl * 4; e += BS) {
+  const int ncx = from_zero ? 0 : ncl;
+  for (int e = tid; e < ncx * 4; e += BS) {
     const int ci = e / 4, i = e % 4;
     const int cell = pc[c0 + ci];
     if (i == 0) cellid[ci] = cell;
@@ -924,7 +927,7 @@ __global__ void __launch_bounds__(BS) k_patch_gs3(Level3View<TS> L, const int* _
       if (pf[f0 + q] == dof) sl = q;
     slot[ci][i] = dof < 0 ? -1 : sl;
   }
-  for (int e = tid; e < ncl * nK; e += BS) {
+  for (int e = tid; e < ncx * nK; e += BS) {
     const int ci = e / nK, i = e % nK;
     const int dof = L.cell_dofs[4 * pc[c0 + ci] + i / m3];
     xs[ci][i] = dof < 0 ? 0.0 : x[(long)dof * m3 + i % m3];
@@ -935,7 +938,7 @@ __global__ void __launch_bounds__(BS) k_patch_gs3(Level3View<TS> L, const int* _
     side[1][q] = 0.0;
   }
   __syncthreads();
-  const int nitem = ncl * 2 * m3;
+  const int nitem = ncx * 2 * m3;
   for (int it = tid; it < nitem; it += BS) {
     const int ci = it / (2 * m3), which = (it / m3) % 2, rr = it % m3;
     int i = -1, cnt = 0;
@@ -991,14 +994,6 @@ __global__ void __launch_bounds__(BS) k_patch_gs3(Level3View<TS> L, const int* _
   }
 }
 
-// The same colour phase at lowest order (one mode per face component: 3
-// unknowns per face, 12 per cell), a wavefront per patch.  Records built at
-// set-up give, per patch cell, the cell's four face numbers and the cell
-// with its two patch faces (local index, slot in the patch, side), so every
-// load depends on at most two earlier ones (the patch's ranges, then its
-// records and face list), and each lane issues its twelve row entries,
-// twelve cell values and its row of the patch inverse together.  The
-// arithmetic, and its order, are those of k_patch_gs3 at one face mode.
 // One item of the lowest-order phase below: row rr of the patch face
 // `which` of patch cell (dv, cc), S_K row times x_K (+ the AL term when it is
 // kept apart), into side[sd][slot].
@@ -1050,13 +1045,15 @@ __device__ __forceinline__ void gs3_lo_item(const Level3View<TS>& L, bool live, 
 // load depends on at most two earlier ones (the patch's ranges, then its
 // records and face list), and each lane issues its twelve row entries,
 // twelve cell values and its row of the patch inverse together.  The
-// arithmetic, and its order, are those of k_patch_gs3 at one face mode.
+// arithmetic, and its order, are those of k_patch_gs3 at one face mode
+// (from_zero as there: the items are skipped).
 template <typename TS, typename TP>
 __global__ void __launch_bounds__(64) k_patch_gs3_lo(Level3View<TS> L, const int* __restrict__ pf_ptr,
                                                      const int* __restrict__ pf, const int* __restrict__ pc_ptr,
                                                      const int4* __restrict__ pdofs, const int2* __restrict__ pcode,
                                                      const long* __restrict__ poff, const TP* __restrict__ pinv,
-                                                     int p0, double* x, const double* __restrict__ b) {
+                                                     int p0, double* x, const double* __restrict__ b,
+                                                     int from_zero) {
   __shared__ double res[PMAX_FACES * 3];
   __shared__ double side[2][PMAX_FACES * 3];
   const int p = p0 + blockIdx.x, lane = threadIdx.x;
@@ -1087,8 +1084,8 @@ __global__ void __launch_bounds__(64) k_patch_gs3_lo(Level3View<TS> L, const int
     side[1][lane] = 0.0;
   }
   __syncthreads();
-  gs3_lo_item(L, lane < nit, (lane / 3) & 1, lane % 3, dvA, ccA, x, side);
-  if (nit > 64) {  // more than ten cells around the edge
+  if (!from_zero) gs3_lo_item(L, lane < nit, (lane / 3) & 1, lane % 3, dvA, ccA, x, side);
+  if (!from_zero && nit > 64) {  // more than ten cells around the edge
     const int it = 64 + lane;
     const int ci = min(it / 6, ncl - 1);
     gs3_lo_item(L, it < nit, (it / 3) & 1, it % 3, pdofs[c0 + ci], pcode[c0 + ci], x, side);
@@ -1258,13 +1255,13 @@ void launch_patch_inverse3(hipStream_t st, Level3View<double> L, const int* pf_p
 template <typename TS, typename TP>
 void launch_patch_gs3(hipStream_t st, Level3View<TS> L, const int* pf_ptr, const int* pf, const int* pc_ptr,
                       const int* pc, const long* poff, const TP* pinv, int p0, int p1, double* x,
-                      const double* b) {
+                      const double* b, bool from_zero) {
   if (p1 <= p0) return;
   // lowest-order patches (at most 36 unknowns): a wavefront each; order k:
   // a workgroup of NT with LDS for the level's face modes
 #define GS3(B, M)                                                                                          \
   hipLaunchKernelGGL((k_patch_gs3<TS, TP, B, M>), dim3(p1 - p0), dim3(B), 0, st, L, pf_ptr, pf, pc_ptr, pc, poff, \
-                     pinv, p0, x, b)
+                     pinv, p0, x, b, from_zero ? 1 : 0)
   if (L.mF == 1)
     GS3(64, 1);
   else if (L.mF <= 3)
@@ -1277,32 +1274,32 @@ void launch_patch_gs3(hipStream_t st, Level3View<TS> L, const int* pf_ptr, const
 }
 template void launch_patch_gs3<double, double>(hipStream_t, Level3View<double>, const int*, const int*, const int*,
                                                const int*, const long*, const double*, int, int, double*,
-                                               const double*);
+                                               const double*, bool);
 template void launch_patch_gs3<float, float>(hipStream_t, Level3View<float>, const int*, const int*, const int*,
                                              const int*, const long*, const float*, int, int, double*,
-                                             const double*);
+                                             const double*, bool);
 template void launch_patch_gs3<float, double>(hipStream_t, Level3View<float>, const int*, const int*, const int*,
                                               const int*, const long*, const double*, int, int, double*,
-                                              const double*);
+                                              const double*, bool);
 
 template <typename TS, typename TP>
 void launch_patch_gs3_lo(hipStream_t st, Level3View<TS> L, const int* pf_ptr, const int* pf, const int* pc_ptr,
                          const int* pdofs, const int* pcode, const long* poff, const TP* pinv, int p0, int p1,
-                         double* x, const double* b) {
+                         double* x, const double* b, bool from_zero) {
   if (p1 <= p0) return;
   hipLaunchKernelGGL((k_patch_gs3_lo<TS, TP>), dim3(p1 - p0), dim3(64), 0, st, L, pf_ptr, pf, pc_ptr,
                      reinterpret_cast<const int4*>(pdofs), reinterpret_cast<const int2*>(pcode), poff, pinv, p0, x,
-                     b);
+                     b, from_zero ? 1 : 0);
 }
 template void launch_patch_gs3_lo<double, double>(hipStream_t, Level3View<double>, const int*, const int*,
                                                   const int*, const int*, const int*, const long*, const double*,
-                                                  int, int, double*, const double*);
+                                                  int, int, double*, const double*, bool);
 template void launch_patch_gs3_lo<float, float>(hipStream_t, Level3View<float>, const int*, const int*, const int*,
                                                 const int*, const int*, const long*, const float*, int, int,
-                                                double*, const double*);
+                                                double*, const double*, bool);
 template void launch_patch_gs3_lo<float, double>(hipStream_t, Level3View<float>, const int*, const int*,
                                                  const int*, const int*, const int*, const long*, const double*,
-                                                 int, int, double*, const double*);
+                                                 int, int, double*, const double*, bool);
 
 void launch_mode0_extract3(hipStream_t st, int nint, int mF, const double* r, double* g0, double* zero_out) {
   const int n = 3 * nint;

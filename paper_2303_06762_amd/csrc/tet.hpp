@@ -145,11 +145,13 @@ void launch_patch_inverse3(hipStream_t st, Level3View<double> L, const int* pf_p
                            double* ws, double* pinv, int* status);
 // Block Gauss-Seidel on the patches [p0, p1) of one colour:
 // x_s += A_ss^-1 (b - A x)_s, a workgroup per patch.
-// (TS: storage of the cell blocks, TP: of the patch inverses)
+// (TS: storage of the cell blocks, TP: of the patch inverses; from_zero:
+// x is zero on the faces of every patch cell, so (b - A x)_s = b_s and the
+// cell blocks are not read)
 template <typename TS, typename TP>
 void launch_patch_gs3(hipStream_t st, Level3View<TS> L, const int* pf_ptr, const int* pf, const int* pc_ptr,
                       const int* pc, const long* poff, const TP* pinv, int p0, int p1, double* x,
-                      const double* b);
+                      const double* b, bool from_zero = false);
 // The same at lowest order (mF = 1), a wavefront per patch, from per patch
 // cell records in patch-cell order: pdofs [4] = the cell's four interior
 // face numbers (or -1), pcode [2] = the cell and a code packing the local
@@ -160,7 +162,7 @@ void launch_patch_gs3(hipStream_t st, Level3View<TS> L, const int* pf_ptr, const
 template <typename TS, typename TP>
 void launch_patch_gs3_lo(hipStream_t st, Level3View<TS> L, const int* pf_ptr, const int* pf, const int* pc_ptr,
                          const int* pdofs, const int* pcode, const long* poff, const TP* pinv, int p0, int p1,
-                         double* x, const double* b);
+                         double* x, const double* b, bool from_zero = false);
 // Lowest-order part of an order-k skeleton vector (mode 0 of each face
 // component) and its injection.
 void launch_mode0_extract3(hipStream_t st, int nint, int mF, const double* r, double* g0, double* zero_out);
