@@ -35,9 +35,10 @@ struct DevLev3 {
   std::vector<int> colour_ptr, hns;
   int *pf_ptr = nullptr, *pf = nullptr, *pc_ptr = nullptr, *pc = nullptr;
   long* poff = nullptr;
-  // lowest-order edge patches: per patch cell the cell's four face numbers
-  // and (cell, packed patch faces / slots / sides), in patch-cell order
-  int *pdofs = nullptr, *pcode = nullptr;
+  // lowest-order edge patches: one record per patch cell (cell, packed patch
+  // faces / slots / sides / far faces, the far faces' interior numbers), in
+  // patch-cell order
+  int* prec = nullptr;
   long pinv_len = 0;
   double* pinv = nullptr;
   float* pinv32 = nullptr;
@@ -529,21 +530,30 @@ hdgmg_status upload_level(Ctx3* c, const Level3& L, int mF, DevLev3& D) {
   if (mF == 1 && !D.vertex) {
     // records of the lowest-order colour phase (else the general kernel)
     const size_t npc = L.pc.size();
-    std::vector<int> pdofs(4 * npc), pcode(2 * npc);
+    std::vector<int> prec(4 * npc);
     bool ok = true;
     for (int p = 0; p < (int)L.pc_ptr.size() - 1 && ok; ++p) {
       const int f0 = L.pf_ptr[p], nf = L.pf_ptr[p + 1] - f0;
       if (nf < 1 || nf > 12 || L.pc_ptr[p + 1] - L.pc_ptr[p] > 12) ok = false;
       for (int j = L.pc_ptr[p]; j < L.pc_ptr[p + 1] && ok; ++j) {
         const int K = L.pc[j];
-        int code = 15 << 4 | 15 << 8, cnt = 0;
+        int code = 15 << 4 | 15 << 8, cnt = 0, nfar = 0, dfar[2] = {0, 0};
         for (int i = 0; i < 4; ++i) {
           const int dof = L.cell_dofs[4 * K + i];
-          pdofs[4 * (size_t)j + i] = dof;
+          if (dof < 0) continue;  // boundary face: x = 0 there
           int sl = -1;
           for (int q = 0; q < nf; ++q)
-            if (dof >= 0 && L.pf[f0 + q] == dof) sl = q;
-          if (sl < 0) continue;
+            if (L.pf[f0 + q] == dof) sl = q;
+          if (sl < 0) {
+            // an interior face outside the patch (not containing the edge)
+            if (nfar == 2) {
+              ok = false;
+              break;
+            }
+            code |= i << (14 + 2 * nfar);
+            dfar[nfar++] = dof;
+            continue;
+          }
           if (cnt == 2) {
             ok = false;
             break;
@@ -553,14 +563,14 @@ hdgmg_status upload_level(Ctx3* c, const Level3& L, int mF, DevLev3& D) {
                  sd << (12 + cnt);
           ++cnt;
         }
-        pcode[2 * (size_t)j] = K;
-        pcode[2 * (size_t)j + 1] = code;
+        code |= nfar << 18;
+        prec[4 * (size_t)j] = K;
+        prec[4 * (size_t)j + 1] = code;
+        prec[4 * (size_t)j + 2] = dfar[0];
+        prec[4 * (size_t)j + 3] = dfar[1];
       }
     }
-    if (ok && npc > 0) {
-      TRY3(upload(c, &D.pdofs, pdofs));
-      TRY3(upload(c, &D.pcode, pcode));
-    }
+    if (ok && npc > 0) TRY3(upload(c, &D.prec, prec));
   }
   D.hpoff.assign(D.np + 1, 0);
   D.hns.assign(D.np, 0);
@@ -599,7 +609,23 @@ hdgmg_status upload_level(Ctx3* c, const Level3& L, int mF, DevLev3& D) {
       if (D.vertex) {
         D.phase_V[col] += 3.0 * ns;
       } else {
-        D.phase_S[col] += ncl * 2.0 * 3 * mF * D.nK;
+        // direct form: per patch cell the rows of its patch faces times the
+        // columns of its far faces (interior faces outside the patch)
+        for (int j = L.pc_ptr[p]; j < L.pc_ptr[p + 1]; ++j) {
+          const int K = L.pc[j];
+          int npf = 0, nfar = 0;
+          for (int i = 0; i < 4; ++i) {
+            const int dof = L.cell_dofs[4 * K + i];
+            if (dof < 0) continue;
+            bool in = false;
+            for (int q = L.pf_ptr[p]; q < L.pf_ptr[p + 1]; ++q) in = in || L.pf[q] == dof;
+            if (in)
+              ++npf;
+            else
+              ++nfar;
+          }
+          D.phase_S[col] += (double)npf * nfar * 9.0 * mF * mF;
+        }
         D.phase_V[col] += ncl * D.nK + 3.0 * ns;
       }
     }
@@ -738,15 +764,15 @@ void sweep(Ctx3* c, DevLev3& D, double* x, const double* b, bool forward, int cl
     const int p0 = D.colour_ptr[col], p1 = D.colour_ptr[col + 1];
     const bool fz = x_zero && ci == 0;
     const int t = kt_begin(c, cls);
-    if (D.pcode && f32(c) && pinv64(c, D))
-      launch_patch_gs3_lo<float, double>(c->st, view32(c, D), D.pf_ptr, D.pf, D.pc_ptr, D.pdofs, D.pcode, D.poff,
-                                         D.pinv, p0, p1, x, b, fz);
-    else if (D.pcode && f32(c))
-      launch_patch_gs3_lo<float, float>(c->st, view32(c, D), D.pf_ptr, D.pf, D.pc_ptr, D.pdofs, D.pcode, D.poff,
-                                        D.pinv32, p0, p1, x, b, fz);
-    else if (D.pcode)
-      launch_patch_gs3_lo<double, double>(c->st, view<double>(D, D.S), D.pf_ptr, D.pf, D.pc_ptr, D.pdofs, D.pcode,
-                                          D.poff, D.pinv, p0, p1, x, b, fz);
+    if (D.prec && f32(c) && pinv64(c, D))
+      launch_patch_gs3_lo<float, double>(c->st, view32(c, D), D.pf_ptr, D.pf, D.pc_ptr, D.prec, D.poff, D.pinv,
+                                         p0, p1, x, b, fz);
+    else if (D.prec && f32(c))
+      launch_patch_gs3_lo<float, float>(c->st, view32(c, D), D.pf_ptr, D.pf, D.pc_ptr, D.prec, D.poff, D.pinv32,
+                                        p0, p1, x, b, fz);
+    else if (D.prec)
+      launch_patch_gs3_lo<double, double>(c->st, view<double>(D, D.S), D.pf_ptr, D.pf, D.pc_ptr, D.prec, D.poff,
+                                          D.pinv, p0, p1, x, b, fz);
     else if (f32(c) && pinv64(c, D))
       launch_patch_gs3<float, double>(c->st, view32(c, D), D.pf_ptr, D.pf, D.pc_ptr, D.pc, D.poff, D.pinv, p0,
                                       p1, x, b, fz);

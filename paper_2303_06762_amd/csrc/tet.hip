@@ -890,11 +890,15 @@ __global__ void __launch_bounds__(NT) k_patch_inverse3(Level3View<double> L, con
   }
 }
 
-// One edge patch per workgroup of BS threads: x_s += A_ss^-1 (b - A x)_s.
-// Residual rows: each patch cell contributes the rows of its (at most two)
-// patch faces, S_K read along columns (symmetric blocks), eight loads in
-// flight per thread; each face's two cells write their contributions to
-// separate LDS slots, so the residual is b - side0 - side1.
+// One edge patch per workgroup of BS threads, the block Gauss-Seidel step
+// in its direct form x_s = A_ss^-1 (b_s - A_{s,r} x_r), r the unknowns
+// outside the patch (the same value as x_s += A_ss^-1 (b - A x)_s, whose
+// A_ss x_s term cancels).  Each patch cell contributes, for the rows of its
+// (at most two) patch faces, only the columns of its two far faces (the
+// faces that do not contain the edge): half of those rows of S_K, read along
+// columns (symmetric blocks), eight loads in flight per thread.  Each
+// face's two cells write their contributions to separate LDS slots, so the
+// right-hand side is b - side0 - side1.
 template <typename TS, typename TP, int BS, int MFC>
 __global__ void __launch_bounds__(BS) k_patch_gs3(Level3View<TS> L, const int* __restrict__ pf_ptr,
                                                   const int* __restrict__ pf, const int* __restrict__ pc_ptr,
@@ -925,7 +929,7 @@ __global__ void __launch_bounds__(BS) k_patch_gs3(Level3View<TS> L, const int* _
     int sl = -1;
     for (int q = 0; q < nf; ++q)
       if (pf[f0 + q] == dof) sl = q;
-    slot[ci][i] = dof < 0 ? -1 : sl;
+    slot[ci][i] = dof < 0 ? -2 : sl;  // -2: boundary face, -1: interior face outside the patch
   }
   for (int e = tid; e < ncx * nK; e += BS) {
     const int ci = e / nK, i = e % nK;
@@ -941,33 +945,53 @@ __global__ void __launch_bounds__(BS) k_patch_gs3(Level3View<TS> L, const int* _
   const int nitem = ncx * 2 * m3;
   for (int it = tid; it < nitem; it += BS) {
     const int ci = it / (2 * m3), which = (it / m3) % 2, rr = it % m3;
-    int i = -1, cnt = 0;
-    for (int q = 0; q < 4; ++q)
-      if (slot[ci][q] >= 0) {
+    // the patch face `which` of the cell, and its far faces (the interior
+    // faces of the cell outside the patch: the two faces that do not
+    // contain the edge, less boundary faces)
+    int i = -1, cnt = 0, q0 = 0, q1 = 0, nfar = 0;
+    for (int q = 0; q < 4; ++q) {
+      const int sq = slot[ci][q];
+      if (sq >= 0) {
         if (cnt == which) i = q;
         ++cnt;
+      } else if (sq == -1) {
+        if (nfar == 0) q0 = q;
+        else q1 = q;
+        ++nfar;
       }
+    }
     if (i < 0) continue;
     const int cell = cellid[ci];
-    // face i's row block: rows contiguous, columns m3 apart
+    // face i's row block: rows contiguous, columns m3 apart; only the columns
+    // of the far faces (x on the patch faces enters through A_ss)
     const TS* Sc = L.S + (long)cell * nK * nK + (long)i * m3 * nK + rr;
     const double* xc = xs[ci];
+    const int ncol = min(nfar, 2) * m3;  // at most two (a tetrahedron's faces off the edge)
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int col = 0;
-    for (; col + 8 <= nK; col += 8) {
+    int t = 0;
+    for (; t + 8 <= ncol; t += 8) {
       double v[8];
+      int cl[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = (double)Sc[(long)(col + u) * m3];
-      a0 += v[0] * xc[col] + v[4] * xc[col + 4];
-      a1 += v[1] * xc[col + 1] + v[5] * xc[col + 5];
-      a2 += v[2] * xc[col + 2] + v[6] * xc[col + 6];
-      a3 += v[3] * xc[col + 3] + v[7] * xc[col + 7];
+      for (int u = 0; u < 8; ++u) {
+        const int tt = t + u;
+        cl[u] = tt < m3 ? q0 * m3 + tt : q1 * m3 + tt - m3;
+        v[u] = (double)Sc[(long)cl[u] * m3];
+      }
+      a0 += v[0] * xc[cl[0]] + v[4] * xc[cl[4]];
+      a1 += v[1] * xc[cl[1]] + v[5] * xc[cl[5]];
+      a2 += v[2] * xc[cl[2]] + v[6] * xc[cl[6]];
+      a3 += v[3] * xc[cl[3]] + v[7] * xc[cl[7]];
     }
-    for (; col < nK; ++col) a0 += (double)Sc[(long)col * m3] * xc[col];
+    for (; t < ncol; ++t) {
+      const int c = t < m3 ? q0 * m3 + t : q1 * m3 + t - m3;
+      a0 += (double)Sc[(long)c * m3] * xc[c];
+    }
     double acc = (a0 + a1) + (a2 + a3);
     if (L.al > 0.0 && rr == 0) {
       double dx = 0.0;
-      for (int q = 0; q < 4; ++q) dx += L.cdiv[4 * cell + q] * xc[q * m3];
+      if (nfar > 0) dx += L.cdiv[4 * cell + q0] * xc[q0 * m3];
+      if (nfar > 1) dx += L.cdiv[4 * cell + q1] * xc[q1 * m3];
       acc += L.al / L.vol[cell] * L.cdiv[4 * cell + i] * dx;
     }
     const int dof = L.cell_dofs[4 * cell + i];
@@ -990,70 +1014,63 @@ __global__ void __launch_bounds__(BS) k_patch_gs3(Level3View<TS> L, const int* _
       a3 += v3 * res[j + 3];
     }
     for (; j < ns; ++j) a0 += (double)Ai[(long)j * ns + q] * res[j];
-    x[(long)pf[f0 + q / m3] * m3 + q % m3] += (a0 + a1) + (a2 + a3);
+    x[(long)pf[f0 + q / m3] * m3 + q % m3] = (a0 + a1) + (a2 + a3);
   }
 }
 
 // One item of the lowest-order phase below: row rr of the patch face
-// `which` of patch cell (dv, cc), S_K row times x_K (+ the AL term when it is
-// kept apart), into side[sd][slot].
+// `which` of a patch cell (record rc: cell, code, far-face unknowns) times x
+// on the cell's far faces (+ the AL coupling when it is kept apart), into
+// side[sd][slot].  Absent far faces read a valid column and weigh it by 0.
 template <typename TS>
-__device__ __forceinline__ void gs3_lo_item(const Level3View<TS>& L, bool live, int which, int rr, int4 dv,
-                                            int2 cc, const double* x, double (*side)[PMAX_FACES * 3]) {
-  const int cell = cc.x, i = (cc.y >> (2 * which)) & 3, s = (cc.y >> (4 + 4 * which)) & 15,
-            sd = (cc.y >> (12 + which)) & 1;
+__device__ __forceinline__ void gs3_lo_item(const Level3View<TS>& L, bool live, int which, int rr, int4 rc,
+                                            const double* x, double (*side)[PMAX_FACES * 3]) {
+  const int cell = rc.x, code = rc.y;
+  const int i = (code >> (2 * which)) & 3, s = (code >> (4 + 4 * which)) & 15, sd = (code >> (12 + which)) & 1;
+  const int q0 = (code >> 14) & 3, q1 = (code >> 16) & 3, nfar = (code >> 18) & 3;
+  // row rr of face i's row block; column c at c * 3
   const TS* Sc = L.S + (long)cell * 144 + i * 36 + rr;
-  double v[12], xc[12];
+  double v[6], xc[6];
 #pragma unroll
-  for (int u = 0; u < 12; ++u) v[u] = (double)Sc[u * 3];
-  const int d[4] = {dv.x, dv.y, dv.z, dv.w};
+  for (int u = 0; u < 3; ++u) {
+    v[u] = (double)Sc[(q0 * 3 + u) * 3];
+    v[3 + u] = (double)Sc[(q1 * 3 + u) * 3];
+  }
 #pragma unroll
-  for (int f = 0; f < 4; ++f)
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-      const double t = x[(long)max(d[f], 0) * 3 + r];
-      xc[3 * f + r] = d[f] >= 0 ? t : 0.0;
-    }
-  double cd[4] = {0.0, 0.0, 0.0, 0.0}, vK = 1.0;
+  for (int u = 0; u < 3; ++u) {
+    const double t0 = x[(long)max(rc.z, 0) * 3 + u], t1 = x[(long)max(rc.w, 0) * 3 + u];
+    xc[u] = nfar > 0 ? t0 : 0.0;
+    xc[3 + u] = nfar > 1 ? t1 : 0.0;
+  }
+  double cd0 = 0.0, cd1 = 0.0, cdi = 0.0, vK = 1.0;
   if (L.al > 0.0) {
+    double c4[4];
 #pragma unroll
-    for (int f = 0; f < 4; ++f) cd[f] = L.cdiv[4 * cell + f];
+    for (int f = 0; f < 4; ++f) c4[f] = L.cdiv[4 * cell + f];
+    cd0 = q0 == 0 ? c4[0] : q0 == 1 ? c4[1] : q0 == 2 ? c4[2] : c4[3];
+    cd1 = q1 == 0 ? c4[0] : q1 == 1 ? c4[1] : q1 == 2 ? c4[2] : c4[3];
+    cdi = i == 0 ? c4[0] : i == 1 ? c4[1] : i == 2 ? c4[2] : c4[3];
     vK = L.vol[cell];
   }
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-  a0 += v[0] * xc[0] + v[4] * xc[4];
-  a1 += v[1] * xc[1] + v[5] * xc[5];
-  a2 += v[2] * xc[2] + v[6] * xc[6];
-  a3 += v[3] * xc[3] + v[7] * xc[7];
-#pragma unroll
-  for (int u = 8; u < 12; ++u) a0 += v[u] * xc[u];
-  double acc = (a0 + a1) + (a2 + a3);
-  if (L.al > 0.0 && rr == 0) {
-    double dx = 0.0;
-#pragma unroll
-    for (int f = 0; f < 4; ++f) dx += cd[f] * xc[3 * f];
-    const double di = i == 0 ? cd[0] : i == 1 ? cd[1] : i == 2 ? cd[2] : cd[3];
-    acc += L.al / vK * di * dx;
-  }
+  double acc = (v[0] * xc[0] + v[1] * xc[1] + v[2] * xc[2]) + (v[3] * xc[3] + v[4] * xc[4] + v[5] * xc[5]);
+  if (L.al > 0.0 && rr == 0) acc += L.al / vK * cdi * (cd0 * xc[0] + cd1 * xc[3]);
   if (live && s < 15) side[sd][s * 3 + rr] = acc;
 }
 
 // The same colour phase at lowest order (one mode per face component: 3
-// unknowns per face, 12 per cell), a wavefront per patch.  Records built at
-// set-up give, per patch cell, the cell's four face numbers and the cell
-// with its two patch faces (local index, slot in the patch, side), so every
-// load depends on at most two earlier ones (the patch's ranges, then its
-// records and face list), and each lane issues its twelve row entries,
-// twelve cell values and its row of the patch inverse together.  The
-// arithmetic, and its order, are those of k_patch_gs3 at one face mode
-// (from_zero as there: the items are skipped).
+// unknowns per face, 12 per cell), a wavefront per patch.  A record built
+// at set-up per patch cell (the cell; its two patch faces with their slots
+// in the patch and sides; its far faces and their unknown numbers) makes
+// every load at most two round trips deep (the patch's ranges, then its
+// records and face list), and each lane issues its six row entries, six
+// far-face values and its row of the patch inverse together; the direct
+// form as in k_patch_gs3 (from_zero as there: the items are skipped).
 template <typename TS, typename TP>
 __global__ void __launch_bounds__(64) k_patch_gs3_lo(Level3View<TS> L, const int* __restrict__ pf_ptr,
                                                      const int* __restrict__ pf, const int* __restrict__ pc_ptr,
-                                                     const int4* __restrict__ pdofs, const int2* __restrict__ pcode,
-                                                     const long* __restrict__ poff, const TP* __restrict__ pinv,
-                                                     int p0, double* x, const double* __restrict__ b,
-                                                     int from_zero) {
+                                                     const int4* __restrict__ prec, const long* __restrict__ poff,
+                                                     const TP* __restrict__ pinv, int p0, double* x,
+                                                     const double* __restrict__ b, int from_zero) {
   __shared__ double res[PMAX_FACES * 3];
   __shared__ double side[2][PMAX_FACES * 3];
   const int p = p0 + blockIdx.x, lane = threadIdx.x;
@@ -1064,12 +1081,10 @@ __global__ void __launch_bounds__(64) k_patch_gs3_lo(Level3View<TS> L, const int
   if (nf < 1 || nf > PMAX_FACES || ncl < 1 || ncl > PMAX_CELLS) return;  // rejected on the host
   const int ns = 3 * nf, nit = 6 * ncl;
   // first: the face of this lane's patch unknown (lanes past ns: a copy of
-  // the last, unused) and the records of its first item
+  // the last, unused) and the record of its first item
   const int q = min(lane, ns - 1);
   const int fq = pf[f0 + q / 3];
-  const int ciA = min(lane / 6, ncl - 1);
-  const int4 dvA = pdofs[c0 + ciA];
-  const int2 ccA = pcode[c0 + ciA];
+  const int4 rcA = prec[c0 + min(lane / 6, ncl - 1)];
   // then its row of the patch inverse, every column index clamped into the
   // row: the loads carry no branch, so that waiting for any later load does
   // not wait for these (columns past ns are read again and not used)
@@ -1084,11 +1099,10 @@ __global__ void __launch_bounds__(64) k_patch_gs3_lo(Level3View<TS> L, const int
     side[1][lane] = 0.0;
   }
   __syncthreads();
-  if (!from_zero) gs3_lo_item(L, lane < nit, (lane / 3) & 1, lane % 3, dvA, ccA, x, side);
+  if (!from_zero) gs3_lo_item(L, lane < nit, (lane / 3) & 1, lane % 3, rcA, x, side);
   if (!from_zero && nit > 64) {  // more than ten cells around the edge
     const int it = 64 + lane;
-    const int ci = min(it / 6, ncl - 1);
-    gs3_lo_item(L, it < nit, (it / 3) & 1, it % 3, pdofs[c0 + ci], pcode[c0 + ci], x, side);
+    gs3_lo_item(L, it < nit, (it / 3) & 1, it % 3, prec[c0 + min(it / 6, ncl - 1)], x, side);
   }
   __syncthreads();
   if (lane < ns) res[lane] = bq - (side[0][lane] + side[1][lane]);
@@ -1107,7 +1121,7 @@ __global__ void __launch_bounds__(64) k_patch_gs3_lo(Level3View<TS> L, const int
 #pragma unroll
     for (int j = 0; j < 3 * PMAX_FACES; ++j)
       if (j >= n4 && j < ns) a0 += av[j] * res[j];
-    x[xq] += (a0 + a1) + (a2 + a3);
+    x[xq] = (a0 + a1) + (a2 + a3);
   }
 }
 
@@ -1284,22 +1298,21 @@ template void launch_patch_gs3<float, double>(hipStream_t, Level3View<float>, co
 
 template <typename TS, typename TP>
 void launch_patch_gs3_lo(hipStream_t st, Level3View<TS> L, const int* pf_ptr, const int* pf, const int* pc_ptr,
-                         const int* pdofs, const int* pcode, const long* poff, const TP* pinv, int p0, int p1,
-                         double* x, const double* b, bool from_zero) {
+                         const int* prec, const long* poff, const TP* pinv, int p0, int p1, double* x,
+                         const double* b, bool from_zero) {
   if (p1 <= p0) return;
   hipLaunchKernelGGL((k_patch_gs3_lo<TS, TP>), dim3(p1 - p0), dim3(64), 0, st, L, pf_ptr, pf, pc_ptr,
-                     reinterpret_cast<const int4*>(pdofs), reinterpret_cast<const int2*>(pcode), poff, pinv, p0, x,
-                     b, from_zero ? 1 : 0);
+                     reinterpret_cast<const int4*>(prec), poff, pinv, p0, x, b, from_zero ? 1 : 0);
 }
 template void launch_patch_gs3_lo<double, double>(hipStream_t, Level3View<double>, const int*, const int*,
-                                                  const int*, const int*, const int*, const long*, const double*,
-                                                  int, int, double*, const double*, bool);
+                                                  const int*, const int*, const long*, const double*, int, int,
+                                                  double*, const double*, bool);
 template void launch_patch_gs3_lo<float, float>(hipStream_t, Level3View<float>, const int*, const int*, const int*,
-                                                const int*, const int*, const long*, const float*, int, int,
-                                                double*, const double*, bool);
+                                                const int*, const long*, const float*, int, int, double*,
+                                                const double*, bool);
 template void launch_patch_gs3_lo<float, double>(hipStream_t, Level3View<float>, const int*, const int*,
-                                                 const int*, const int*, const int*, const long*, const double*,
-                                                 int, int, double*, const double*, bool);
+                                                 const int*, const int*, const long*, const double*, int, int,
+                                                 double*, const double*, bool);
 
 void launch_mode0_extract3(hipStream_t st, int nint, int mF, const double* r, double* g0, double* zero_out) {
   const int n = 3 * nint;

@@ -144,7 +144,8 @@ void launch_patch_inverse3(hipStream_t st, Level3View<double> L, const int* pf_p
                            const int* pc_ptr, const int* pc, const long* poff, int p0, int np, int ns_max,
                            double* ws, double* pinv, int* status);
 // Block Gauss-Seidel on the patches [p0, p1) of one colour:
-// x_s += A_ss^-1 (b - A x)_s, a workgroup per patch.
+// x_s = A_ss^-1 (b_s - A_{s,r} x_r) (r: the unknowns outside the patch; the
+// same value as x_s += A_ss^-1 (b - A x)_s), a workgroup per patch.
 // (TS: storage of the cell blocks, TP: of the patch inverses; from_zero:
 // x is zero on the faces of every patch cell, so (b - A x)_s = b_s and the
 // cell blocks are not read)
@@ -152,17 +153,18 @@ template <typename TS, typename TP>
 void launch_patch_gs3(hipStream_t st, Level3View<TS> L, const int* pf_ptr, const int* pf, const int* pc_ptr,
                       const int* pc, const long* poff, const TP* pinv, int p0, int p1, double* x,
                       const double* b, bool from_zero = false);
-// The same at lowest order (mF = 1), a wavefront per patch, from per patch
-// cell records in patch-cell order: pdofs [4] = the cell's four interior
-// face numbers (or -1), pcode [2] = the cell and a code packing the local
-// indices i0, i1 (2 bits each, bits 0-3) of its patch faces, their slots in
-// the patch face list (4 bits each, bits 4-11; 15 = none) and their sides
-// (the cell is fcell[2f + side]; bits 12 and 13).  Device arrays, 16- and
-// 8-byte aligned.
+// The same at lowest order (mF = 1), a wavefront per patch, from one record
+// per patch cell in patch-cell order (prec [4] ints, 16-byte aligned): the
+// cell; a code packing the local indices i0, i1 of its patch faces (bits
+// 0-3), their slots in the patch face list (4 bits each, bits 4-11; 15 =
+// none), their sides (the cell is fcell[2f + side]; bits 12, 13), the local
+// indices of its far faces (the interior faces not containing the edge;
+// bits 14-15, 16-17) and their count (bits 18-19); the far faces' interior
+// numbers (0 where absent).
 template <typename TS, typename TP>
 void launch_patch_gs3_lo(hipStream_t st, Level3View<TS> L, const int* pf_ptr, const int* pf, const int* pc_ptr,
-                         const int* pdofs, const int* pcode, const long* poff, const TP* pinv, int p0, int p1,
-                         double* x, const double* b, bool from_zero = false);
+                         const int* prec, const long* poff, const TP* pinv, int p0, int p1, double* x,
+                         const double* b, bool from_zero = false);
 // Lowest-order part of an order-k skeleton vector (mode 0 of each face
 // component) and its injection.
 void launch_mode0_extract3(hipStream_t st, int nint, int mF, const double* r, double* g0, double* zero_out);
