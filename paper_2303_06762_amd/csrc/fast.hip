@@ -23,11 +23,12 @@
 //        patch), 16 consecutive patches per row, so that a wavefront reads
 //        four 16-patch runs per step
 //   Sc   (fused colour phase) per colour, the blocks of each patch's cells
-//        in patch order, NCP slots per patch (zero padding slots): a slot
-//        holds its cell's block with the local facets reordered so that the
-//        facet opposite the patch vertex comes last, and of its packed upper
-//        triangle only the rows of the two patch facets (the last facet's
-//        diagonal block is never needed), fast_cell_words_patch words
+//        in patch order, NCP slots per patch (zero padding slots): with the
+//        cell's local facets reordered so that the facet opposite the patch
+//        vertex (the far facet) comes last, a slot holds the coupling of the
+//        two patch facets to the far facet, rows 0..2 m2 - 1 and columns
+//        2 m2..3 m2 - 1 of the reordered block, row by row,
+//        fast_cell_words_patch words
 //   meta (fused colour phase) per patch of one colour, field-major
 //        ([field][np]): for each cell slot the interior ids of its three
 //        reordered facets (-1 on the boundary and in padding slots), and for
@@ -35,8 +36,9 @@
 //        two patch facets) pairs holding it, one byte each (slot * 4 + place)
 // A Gauss-Seidel colour phase is a cell apply (y = S x for every cell) then
 // k_patch_relax (x_s += A_ss^-1 (b - y)_s for the colour's patches), or one
-// fused kernel (k_patch_gs_fused) that forms the patch residual from the
-// patch's own cells.
+// fused kernel (k_patch_gs_fused) in the direct form of the same step,
+// x_s = A_ss^-1 (b_s - A_{s,r} x_r) (r: the unknowns outside the patch, here
+// those of the far facets; the A_ss x_s term of the other form cancels).
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -268,16 +270,18 @@ __global__ void __launch_bounds__(64) k_patch_relax_wave(int np, const int* __re
 // wavefront per patch (per PPW consecutive patches).  Within a colour the
 // cells around a patch vertex belong to no other patch of the colour, the
 // patch facets to no other patch, and the cells' remaining facets to no
-// patch of the colour at all, so the residual rows of a patch come from its
-// own cells and from x values no other wavefront of the launch changes:
-//   r_s = b_s - sum over the patch cells K of (S_K x_K) on the patch rows,
-//   x_s += A_ss^-1 r_s.
-// The colour's cell blocks are stored patch by patch (Sc, see the layout
-// notes at the top), so a wavefront's blocks and triangles are two
-// contiguous runs, loaded with the metadata in the first round; the x and b
-// gathers wait on the metadata.  Every load is issued before the first LDS
-// store; the triangles go to LDS once the residual no longer needs the
-// blocks, and the update writes x_s from the copy gathered into LDS.
+// patch of the colour at all, so the step needs only the patch's own cells
+// and x values no other wavefront of the launch changes.  In its direct form
+//   g_s = b_s - sum over the patch cells K of (S_K)_{patch facets, far facet} x_far,
+//   x_s = A_ss^-1 g_s
+// (equal to x_s += A_ss^-1 (b - A x)_s: the A_ss x_s term cancels), each
+// cell contributes only the coupling of its two patch facets to its far
+// facet.  The colour's coupling blocks are stored patch by patch (Sc, see
+// the layout notes at the top), so a wavefront's blocks and triangles are
+// two contiguous runs, loaded with the metadata in the first round; the x
+// (far facets) and b gathers wait on the metadata.  Every load is issued
+// before the first LDS store; the triangles go to LDS once the right-hand
+// side no longer needs the blocks.
 // 16-byte words as a native vector (plain loads and stores, kept in
 // registers)
 typedef unsigned int U4 __attribute__((ext_vector_type(4)));
@@ -289,7 +293,7 @@ struct FusedShape {
   static constexpr int T16 = PPW * PW * (int)sizeof(TS) / 16;  // the wavefront's triangles
   static constexpr int C16 = PPW * NCP * CR * (int)sizeof(TS) / 16;  // ... and cell blocks
   static constexpr int NCELL = PPW * NCP;
-  static constexpr int NX = NCELL * NK;  // the cells' x values
+  static constexpr int NX = NCELL * M2;  // x on the cells' far facets
   static constexpr int NLT = (T16 + 63) / 64, NLC = (C16 + 63) / 64, NLX = (NX + 63) / 64;
 };
 // (LDS holds about 16 wavefronts per CU; four per SIMD leave 128 registers,
@@ -316,13 +320,13 @@ k_patch_gs_fused(int np, const int* __restrict__ pf, const int* __restrict__ met
   const int p = p0 + lp;
   const bool on = lp < PPW && p < np;
   // metadata first, every load unconditional (indices clamped into the
-  // colour; what a lane of a padding patch reads is never used): the x
-  // items' facets, the patch rows' facet and sides
+  // colour; what a lane of a padding patch reads is never used): the far
+  // facets of the x items, the patch rows' facet and sides
   int xf[F::NLX];
 #pragma unroll
   for (int q = 0; q < F::NLX; ++q) {
-    const int t = min(lane + 64 * q, NX - 1), j = t / NK, lf = (t % NK) / M2;
-    xf[q] = meta[((j % NCP) * 3 + lf) * np + min(p0 + j / NCP, np - 1)];
+    const int t = min(lane + 64 * q, NX - 1), j = t / M2;
+    xf[q] = meta[((j % NCP) * 3 + 2) * np + min(p0 + j / NCP, np - 1)];
   }
   const int pc = min(p, np - 1);
   const int fr = pf[(i / M2) * np + pc];
@@ -361,14 +365,13 @@ k_patch_gs_fused(int np, const int* __restrict__ pf, const int* __restrict__ met
   // statement that takes both in registers keeps their loads with the others
   asm volatile("" ::"v"(bv), "v"(ps));
   __syncthreads();
-  double xrow;
-  // residual rows: lane (patch, row i = facet slot * M2 + c).  Every lane
-  // computes one without branches (so that the loads above stay ahead of
-  // the stores); lanes past the wavefront's patches and padding rows keep
-  // their slots and rows in range and discard the result.  A side's code
-  // is slot * 4 + its place (0 or 1) among the cell's two patch facets;
-  // row a < 2 M2 of a slot holds entries (a, b >= a) at
-  // e(a, b) = a NK - a (a - 1) / 2 + b - a, and (b < a, a) sits in row b.
+  // right-hand side rows: lane (patch, row i = facet slot * M2 + c).  Every
+  // lane computes one without branches (so that the loads above stay ahead
+  // of the stores); lanes past the wavefront's patches and padding rows
+  // keep their slots and rows in range and discard the result.  A side's
+  // code is slot * 4 + its place (0 or 1) among the cell's two patch
+  // facets; row a < 2 M2 of a slot couples to the far facet's M2 values
+  // (entry (a, c') at a M2 + c').
   {
     const int lpc = min(lp, PPW - 1);
     double y = 0.0;
@@ -376,20 +379,13 @@ k_patch_gs_fused(int np, const int* __restrict__ pf, const int* __restrict__ met
     for (int s = 0; s < 2; ++s) {
       const int code = (ps >> (8 * s)) & 0xff;
       const int slot = lpc * NCP + min(code >> 2, NCP - 1), row = min(code & 3, 1) * M2 + c;
-      const TS* S = (const TS*)Bs + slot * CR;
-      const double* xk = xs + slot * NK;
-      const int ro = row * NK - row * (row - 1) / 2 - row;
+      const TS* S = (const TS*)Bs + slot * CR + row * M2;
+      const double* xk = xs + slot * M2;
 #pragma unroll
-      for (int bb = 0; bb < NK; ++bb) {
-        const int e = bb >= row ? ro + bb : bb * NK - bb * (bb - 1) / 2 - bb + row;
-        y += (double)S[e] * xk[bb];
-      }
+      for (int bb = 0; bb < M2; ++bb) y += (double)S[bb] * xk[bb];
     }
     const double r = f >= 0 ? bv - y : 0.0;
     if (lp < PPW) rs[lane] = r;
-    // x on the row (as gathered into the first side's cell)
-    const int code = ps & 0xff;
-    xrow = xs[(lpc * NCP + min(code >> 2, NCP - 1)) * NK + min(code & 3, 1) * M2 + c];
   }
   __syncthreads();
 #pragma unroll
@@ -406,14 +402,14 @@ k_patch_gs_fused(int np, const int* __restrict__ pf, const int* __restrict__ met
     const int e = j < i ? colj + i : rowi + j;
     d += (double)A[e] * rr[j];
   }
-  if (f >= 0) x[(long)f * M2 + c] = xrow + d;
+  if (f >= 0) x[(long)f * M2 + c] = d;
 }
 
 // Full row-major FP64 cell blocks -> the patch-ordered slots of one colour:
 // slot t holds cell K = code >> 2 with its local facets reordered as (the
-// two others in increasing order, far = code & 3), the rows of the first
-// two reordered facets of the packed upper triangle; code < 0 (padding):
-// zeros.
+// two others in increasing order, far = code & 3), the coupling of the
+// first two reordered facets to the far facet (row a < 2 m2, column c < m2
+// at a m2 + c); code < 0 (padding): zeros.
 template <typename TS>
 __global__ void k_pack_cells_patch(int nslot, int m2, int cr, const int* __restrict__ code,
                                    const double* __restrict__ S, TS* __restrict__ Sc) {
@@ -424,11 +420,10 @@ __global__ void k_pack_cells_patch(int nslot, int m2, int cr, const int* __restr
   int e = 0;
   if (cd >= 0) {
     const int K = cd >> 2, far = cd & 3;
-    const int perm[3] = {far == 0 ? 1 : 0, far == 2 ? 1 : 2, far};
+    const int perm[2] = {far == 0 ? 1 : 0, far == 2 ? 1 : 2};
     const double* B = S + (long)K * nK * nK;
     for (int a = 0; a < 2 * m2; ++a)
-      for (int c = a; c < nK; ++c, ++e)
-        out[e] = (TS)B[(perm[a / m2] * m2 + a % m2) * nK + perm[c / m2] * m2 + c % m2];
+      for (int c = 0; c < m2; ++c, ++e) out[e] = (TS)B[(perm[a / m2] * m2 + a % m2) * nK + far * m2 + c];
   }
   for (; e < cr; ++e) out[e] = (TS)0;
 }

@@ -22,12 +22,12 @@ inline long fast_cell_words(int nK, bool full = false) {
 }
 inline long fast_cell_words16(int nK) { return ((long)nK * (nK + 1) / 2 + 7) / 8 * 8; }
 
-// Words of one slot of the fused colour phase's cell storage: the rows of
-// two of the three facets (2 m2 rows of the reordered 3 m2 x 3 m2 block)
-// of the packed upper triangle, rounded up to whole 16-byte groups (word:
-// bytes per word).
+// Words of one slot of the fused colour phase's cell storage: the coupling
+// of the two patch facets to the far facet (the 2 m2 x m2 block of rows
+// 0..2 m2 - 1 and columns 2 m2..3 m2 - 1 of the reordered block), row by
+// row, rounded up to whole 16-byte groups (word: bytes per word).
 __host__ __device__ constexpr int fast_cell_words_patch(int m2, int word) {
-  return ((2 * m2 * 3 * m2 - 2 * m2 * (2 * m2 - 1) / 2) * word + 15) / 16 * 16 / word;
+  return (2 * m2 * m2 * word + 15) / 16 * 16 / word;
 }
 
 // Patch-inverse storage of the zero-padded NS = FAST_NF*m2 square inverses:

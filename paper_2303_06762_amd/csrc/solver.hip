@@ -625,10 +625,11 @@ hdgmg_status setup_fused(hdgmg_ctx* ctx, const Level& L, DevLevel& D) {
     }
     metas.push_back(std::move(meta));
     codes.push_back(std::move(code));
-    // the triangles, the cell slots as stored, metadata and facet lists,
-    // b and x once per patch facet, x once per far facet, the update of x
-    bytes.push_back((double)np * pw * ws + (double)np * ncp * cr * ws + (double)np * (nfield + FAST_NF) * 4.0 +
-                    (3.0 * nfac + nfar) * m2 * 8.0);
+    // the triangles, the coupling blocks as stored, the metadata read (far
+    // facet per slot, patch facets, sides), b once per patch facet, x once
+    // per far facet, the update of x
+    bytes.push_back((double)np * pw * ws + (double)np * ncp * cr * ws + (double)np * (ncp + 2 * FAST_NF) * 4.0 +
+                    (2.0 * nfac + nfar) * m2 * 8.0);
   }
   for (int cc = 0; cc < L.ncol; ++cc) {
     int *dm, *dc;

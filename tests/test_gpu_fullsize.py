@@ -187,11 +187,15 @@ def test_preconditioner_symmetric_positive(solvers):
 
 @pytest.mark.parametrize("prec", [0, 1])
 def test_fused_colour_phase_matches_the_pair(solvers, prec):
-    """The default order-k colour phase (one launch per colour that forms
-    each patch residual from the patch's own cells) against the
-    cell-apply / patch-relaxation pair it replaces: the same MG_hp up to the
-    summation order of the residual rows, and no order-k cell apply in the
-    colour phases (the pair has one per phase after the first)."""
+    """The default order-k colour phase (one launch per colour, the block
+    Gauss-Seidel step in its direct form x_s = A_ss^-1 (b_s - A_{s,r} x_r)
+    from the patch's own cells) against the cell-apply / patch-relaxation
+    pair (x_s += A_ss^-1 (b - A x)_s): the same MG_hp up to rounding, and no
+    order-k cell apply in the colour phases (the pair has one per phase
+    after the first).  In FP64 the two agree to 1e-12.  With FP32 storage
+    the stored patch inverse multiplies the whole right-hand side in one
+    form and the residual in the other, so they agree to FP32 rounding
+    amplified by the patch condition numbers (measured 4.2e-6; bar 2e-5)."""
     import paper_2303_06762_amd as hd
     c, t = synth.kuhn_square(4)
     _note(f"[fullsize] fused colour phase vs pair, vcycle_precision {prec}")
@@ -209,7 +213,7 @@ def test_fused_colour_phase_matches_the_pair(solvers, prec):
     pair.close()
     diff = (torch.linalg.norm(z["fused"] - z["pair"]) / torch.linalg.norm(z["pair"])).item()
     _note(f"  rel. difference {diff:.2e}, order-k cell applies {launches}")
-    assert diff <= 1e-12, diff
+    assert diff <= (1e-12 if prec == 0 else 2e-5), diff
     # the pair applies the cells in every colour phase but the first one from
     # zero: 2 m_relax n_colours - 1 = 5 more order-k cell applies
     assert launches["pair"] - launches["fused"] == 5, launches
