@@ -33,7 +33,7 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP64_MFMA_TFS = 78.6
 KCLASS3 = {0: "order-k edge-patch Gauss-Seidel, one colour (k_patch_gs3)",
            1: "order-k skeleton apply S_K x_K (k_cell_apply3 + k_face_gather3)",
-           2: "lowest-order edge-patch Gauss-Seidel phases (k_patch_gs3, m_F = 1)",
+           2: "lowest-order edge-patch Gauss-Seidel phases (k_patch_gs3_lo)",
            3: "MG_hp"}
 KCLASS = {0: "order-k vertex-patch Gauss-Seidel, one colour phase (k_patch_gs_fused; "
              "k_patch_relax_wave for the first phase from zero)",
@@ -435,7 +435,7 @@ def sweep(hd, synth, torch, np, c, t, a):
 # known size (FETCH_SIZE counts 0.500 of the bytes read, WRITE_SIZE 1.000 of
 # those written on this part); the summary, with its commands, is in
 # COUNTER_SOURCE.  Retake them whenever the kernel changes.
-COUNTER_TRAFFIC = {("order-k edge-patch Gauss-Seidel, one colour (k_patch_gs3)", 3): 10.856e9 + 0.027e9}
+COUNTER_TRAFFIC = {("order-k edge-patch Gauss-Seidel, one colour (k_patch_gs3)", 3): 7.278e9 + 0.027e9}
 COUNTER_SOURCE = "profiles/k_patch_gs3_fp64_k3_32cube.md"
 
 
@@ -506,8 +506,9 @@ def vcycle3(m):
             "implementation_GB": m["vc_design"] / 1e9, "implementation_GB_per_s": m["vc_design"] / avg / 1e9,
             "model": "compulsory = every stored operator read once per use in packed symmetric form (cell "
                      "blocks, edge-patch inverses, CR blocks, coarsest inverse) + vectors + transfers; "
-                     "implementation = what the launches move (each patch cell's two patch-face row blocks "
-                     "of S_K per edge patch, i.e. S_K read three times per sweep, full patch inverses)"}
+                     "implementation = what the launches move (per edge patch and patch cell the coupling "
+                     "of its two patch faces to its two far faces, a quarter of S_K, so S_K is read 1.5 "
+                     "times per sweep; full patch inverses)"}
 
 
 def stokes2d_line(hd, synth, torch, np, a):
@@ -737,9 +738,11 @@ def main():
                      "traffic_source": COUNTER_SOURCE if (KCLASS3[by_time], a.k) in COUNTER_TRAFFIC else None,
                      "kernel": KCLASS3[by_time], "launches": n_l, "avg_us": 1e3 * ms / n_l,
                      "algorithmic_bytes_per_launch": by / n_l,
-                     "bytes_model": "per colour phase: for each edge patch its inverse and, for each patch "
-                                    "cell, the two patch-face row blocks of S_K, each entry read once in the "
-                                    "stored (FP64, full) layout, plus the patch's vectors",
+                     "bytes_model": "per colour phase (block Gauss-Seidel in the direct form x_s = "
+                                    "A_ss^-1 (b_s - A_sr x_r)): for each edge patch its inverse and, for each "
+                                    "patch cell, the coupling of its patch faces to its far faces in S_K, each "
+                                    "entry read once in the stored (FP64, full) layout, plus the patch's "
+                                    "vectors; the first phase from zero: inverses and vectors only",
                      "copy_GB_per_s": copy_gbs},
         "vcycle": vcycle3(m64),
         "kernel_classes": classes3(tm),
