@@ -64,16 +64,18 @@ template <typename TS>
 void launch_patch_relax(hipStream_t st, int m2, int np, const int* pf, const TS* Pp, const double* b,
                         const double* yF, double* x, bool full = true, const float* sc = nullptr,
                         const KernelEvents* ev = nullptr);
-// One Gauss-Seidel colour phase of symmetric operators in one launch
-// (x_s += A_ss^-1 (b - A x)_s for the np patches of the colour), from the
-// patches' upper-triangle inverses Pp, the colour's patch-ordered cell
-// slots Sc and its metadata (see fast.hip); m2 in {2, 4, 6} and ncp in {6, 7}
-// slots per patch (fast_fused_supported).
+// One Gauss-Seidel colour phase of symmetric operators in one launch, in
+// the direct form x_s = A_ss^-1 (b_s - A_{s,r} x_r) for the np patches of
+// the colour (r: the far facets of the patch cells), from the patches'
+// upper-triangle inverses Pp, the colour's patch-ordered coupling slots Sc
+// and its metadata (see fast.hip); m2 in {2, 4, 6} and ncp in {6, 7} slots
+// per patch (fast_fused_supported).
 bool fast_fused_supported(int m2, int ncp);
 template <typename TS>
 void launch_patch_gs_fused(hipStream_t st, int m2, int ncp, int np, const int* pf, const int* meta, const TS* Pp,
                            const TS* Sc, const double* b, double* x, const KernelEvents* ev = nullptr);
-// Full row-major FP64 blocks S [nc][3 m2][3 m2] -> one colour's slots:
+// Full row-major FP64 blocks S [nc][3 m2][3 m2] -> one colour's slots (the
+// coupling of each cell's two patch facets to its far facet):
 // code[t] = cell * 4 + local index of the facet opposite the patch vertex,
 // or -1 for a padding slot.
 template <typename TS>
