@@ -629,6 +629,8 @@ def main():
     ap.add_argument("--tables", choices=["cavity", "step"], default=None,
                     help="the paper's Stokes and Navier-Stokes cavity or step runs (one JSON line per case)")
     ap.add_argument("--profile-solves", type=int, default=2)
+    ap.add_argument("--profile-prec", type=int, default=0, choices=[0, 1, 2, 3],
+                    help="vcycle_precision of the profile run (2: triangles only; 3: tetrahedra only)")
     ap.add_argument("--profile-dim", type=int, default=3, choices=[2, 3],
                     help="--profile-run on the tetrahedral cube (3) or the 256x256 triangle workload (2)")
     ap.add_argument("--profile-run", action="store_true",
@@ -669,10 +671,11 @@ def main():
         del src, dst
         if a.profile_dim == 2:
             # the triangle workload of the 2D line: 256x256, k = 2, gamma = 1e2
-            s = hd.Solver(c, t, a.n_refine, 2, 1.0, 1.0, 1e2, atol=0.0)
+            s = hd.Solver(c, t, a.n_refine, 2, 1.0, 1.0, 1e2, atol=0.0, vcycle_precision=a.profile_prec)
         else:
             c3, t3 = synth.kuhn_cube(4)
-            s = hd.Solver(c3, t3, 3, a.k, 1.0, 1.0, 1e3, atol=0.0, m_relax=2, m_smooth=2)
+            s = hd.Solver(c3, t3, 3, a.k, 1.0, 1.0, 1e3, atol=0.0, m_relax=2, m_smooth=2,
+                          vcycle_precision=a.profile_prec)
         s.assemble()
         g = torch.ones(s.n_skel, dtype=torch.float64, device="cuda")
         x = torch.empty_like(g)

@@ -182,17 +182,22 @@ typedef struct {
                               same codes                                   */
   int fused_phase;         /* 1 (default): on every streamed level of a
                               triangle mesh with symmetric blocks (the
-                              order-k level for k <= 2 and the lowest-order
-                              levels; vcycle_precision 0 or 1; vertex
-                              patches of at most 7 cells) a Gauss-Seidel
-                              colour phase is one launch that forms each
-                              patch's residual from its own cells, read
-                              from a per-colour, patch-ordered copy of the
-                              blocks; such lowest-order levels use it in
-                              place of the record kernel.  0: the
-                              cell-apply / patch-relaxation pair (records
-                              on the lowest-order levels).  Same iterates
-                              up to rounding; ignored on tetrahedra       */
+                              order-k level for k <= 2 with
+                              vcycle_precision 0 or 1, and the
+                              lowest-order levels; vertex patches of at
+                              most 7 cells) a Gauss-Seidel colour phase is
+                              one launch that takes the step in its direct
+                              form x_s = A_ss^-1 (b_s - A_{s,r} x_r) from
+                              the patch's own cells, read from a
+                              per-colour, patch-ordered copy of their
+                              coupling blocks; such lowest-order levels
+                              use it in place of the record kernel.  0:
+                              the cell-apply / patch-relaxation pair
+                              (records on the lowest-order levels).  Same
+                              iterates up to rounding (FP64; with FP32
+                              storage the two forms agree to FP32
+                              rounding amplified by the patch condition
+                              numbers); ignored on tetrahedra             */
 } hdgmg_opts;
 
 /* Defaults: m_p = m_h = 1, V-cycle, growth 2, rtol 1e-8, atol 1e-10,

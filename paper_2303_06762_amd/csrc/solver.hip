@@ -558,11 +558,14 @@ hdgmg_status upload_level(hdgmg_ctx* ctx, const Level& L, int m, DevLevel& D) {
 }
 
 // Metadata, byte model and patch-ordered cell storage of the fused colour
-// phase on the order-k level, when its streaming layout is symmetric and
-// packed, the V-cycle stores FP64 or FP32, and every patch has at most 7
-// cells (else the level keeps the cell-apply / patch-relaxation pair).
+// phase on a streamed level, when its streaming layout is symmetric and
+// packed, the level is stored FP64 or FP32 (with vcycle_precision 2 the
+// order-k level keeps FP16 blocks and the pair; the lowest-order levels are
+// FP32), and every patch has at most 7 cells (else the level keeps the
+// cell-apply / patch-relaxation pair).
 hdgmg_status setup_fused(hdgmg_ctx* ctx, const Level& L, DevLevel& D) {
-  if (!D.fast || D.full || D.pfull || !fast_cell_packed(D.nK, false) || ctx->opts.vcycle_precision > 1)
+  if (!D.fast || D.full || D.pfull || !fast_cell_packed(D.nK, false) ||
+      (ctx->opts.vcycle_precision > 1 && &D == &ctx->K))
     return HDGMG_OK;
   int maxc = 0;
   for (int p = 0; p < D.npatch; ++p) maxc = std::max(maxc, L.patch_cell_ptr[p + 1] - L.patch_cell_ptr[p]);
