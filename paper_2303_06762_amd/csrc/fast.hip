@@ -303,9 +303,9 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4)))
 k_patch_gs_fused(int np, const int* __restrict__ pf, const int* __restrict__ meta, const TS* __restrict__ Pp,
                  const TS* __restrict__ Sc, const double* __restrict__ b, double* __restrict__ x) {
   using F = FusedShape<M2, NCP, TS>;
-  constexpr int NS = F::NS, NK = F::NK, PPW = F::PPW, PW = F::PW, CR = F::CR;
+  constexpr int NS = F::NS, PPW = F::PPW, PW = F::PW, CR = F::CR;
   constexpr int T16 = F::T16, C16 = F::C16, NX = F::NX;
-  __shared__ U4 Bs[T16 > C16 ? T16 : C16];  // the cell blocks, then the triangles
+  __shared__ U4 Bs[T16 > C16 ? T16 : C16];  // the coupling blocks, then the triangles
   __shared__ double xs[NX];
   __shared__ double rs[PPW * NS];
   const int lane = threadIdx.x;

@@ -506,7 +506,7 @@ hdgmg_status upload_level(hdgmg_ctx* ctx, const Level& L, int m, DevLevel& D) {
   D.full = ctx->opts.oseen != 0;
   D.sp_words = fast_cell_words(D.nK, D.full);
   if (D.fast) {
-    const int m2 = 2 * m, nK = D.nK;
+    const int m2 = 2 * m;
     std::vector<int> cd(3 * (size_t)L.nc, -1);
     double ncd = 0;
     for (int c = 0; c < L.nc; ++c)
