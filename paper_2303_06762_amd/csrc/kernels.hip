@@ -739,6 +739,48 @@ __global__ void k_ell_spmv_g(int n, int w, const int* __restrict__ ci, const TS*
 }
 
 
+// The same grouped product on a sliced ELL matrix: the rows in slices of
+// H = 64 / L (the rows one wavefront covers), each slice padded only to its
+// own widest row (sw[s] slots; entry (slot k, row sH + rr) at
+// soff[s] + k H + rr), so that rows of different lengths in different
+// slices (the prolongations' rows inside a coarse cell against those on its
+// facets) stop paying for the widest row of the matrix.
+template <typename TS, int L>
+__global__ void k_sell_spmv_g(int n, const long* __restrict__ soff, const int* __restrict__ sw,
+                              const int* __restrict__ ci, const TS* __restrict__ v, const double* __restrict__ x,
+                              double* y, double beta_y, double* zero_out) {
+  constexpr int H = 64 / L;
+  const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long r = tid / L;
+  const int j = (int)(tid % L);
+  const bool ok = r < n;  // every lane stays for the shuffles
+  double s = 0.0;
+  if (ok) {
+    const long sl = r / H;
+    const long base = soff[sl] + (r - sl * H);
+    const int w = sw[sl];
+    for (int k0 = j; k0 < w; k0 += 8 * L) {
+      TS vv[8];
+      int cc[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int k = k0 + q * L;
+        const long e = base + (long)min(k, w - 1) * H;
+        vv[q] = v[e] * (TS)(k < w);
+        cc[q] = ci[e];
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) s += (double)vv[q] * x[cc[q]];
+    }
+  }
+#pragma unroll
+  for (int off = L / 2; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if (ok && j == 0) {
+    if (zero_out) zero_out[r] = 0.0;
+    y[r] = beta_y == 0.0 ? s : beta_y * y[r] + s;
+  }
+}
+
 // y = A x for a dense row-major A (n x n, storage TS, row stride ld: a
 // multiple of 4, zero-padded), a wavefront per row: each lane reads four
 // consecutive entries per 16-byte load (two for FP64), eight such loads in
@@ -1168,6 +1210,26 @@ template void launch_ell_spmv<double>(hipStream_t, int, int, const int*, const d
                                       double, double*);
 template void launch_ell_spmv<float>(hipStream_t, int, int, const int*, const float*, const double*, double*,
                                      double, double*);
+int sell_lanes(int w) { return w <= 8 ? 0 : w <= 16 ? 2 : w <= 32 ? 4 : 8; }
+template <typename TS>
+void launch_sell_spmv(hipStream_t st, int n, int L, const long* soff, const int* sw, const int* ci, const TS* v,
+                      const double* x, double* y, double beta_y, double* zero_out) {
+  if (n <= 0) return;
+  const long nt = (long)L * n;
+  if (L == 2)
+    hipLaunchKernelGGL((k_sell_spmv_g<TS, 2>), dim3(nblk(nt)), dim3(TPB), 0, st, n, soff, sw, ci, v, x, y, beta_y,
+                       zero_out);
+  else if (L == 4)
+    hipLaunchKernelGGL((k_sell_spmv_g<TS, 4>), dim3(nblk(nt)), dim3(TPB), 0, st, n, soff, sw, ci, v, x, y, beta_y,
+                       zero_out);
+  else
+    hipLaunchKernelGGL((k_sell_spmv_g<TS, 8>), dim3(nblk(nt)), dim3(TPB), 0, st, n, soff, sw, ci, v, x, y, beta_y,
+                       zero_out);
+}
+template void launch_sell_spmv<double>(hipStream_t, int, int, const long*, const int*, const int*, const double*,
+                                       const double*, double*, double, double*);
+template void launch_sell_spmv<float>(hipStream_t, int, int, const long*, const int*, const int*, const float*,
+                                      const double*, double*, double, double*);
 template <typename TS>
 void launch_gemv_rows(hipStream_t st, int n, int ld, const TS* A, const double* x, double* y) {
   if (n > 0) hipLaunchKernelGGL(k_gemv_rows<TS>, dim3((n + 3) / 4), dim3(256), 0, st, n, ld, A, x, y);

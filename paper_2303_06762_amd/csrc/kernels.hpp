@@ -144,6 +144,14 @@ void launch_mode0_residual(hipStream_t st, int nc, int nint, int m, const int* c
 template <typename TS>
 void launch_ell_spmv(hipStream_t st, int n, int w, const int* ci, const TS* v, const double* x, double* y,
                      double beta_y, double* zero_out = nullptr);
+// The same for a sliced ELL matrix with L lanes per row (sell_lanes of its
+// widest row: 2, 4 or 8; 0 when every row has at most 8 entries, for which
+// the plain ELL kernel is used): rows in slices of 64 / L, slice s padded to
+// its own width sw[s], entry (slot k, row s H + rr) at soff[s] + k H + rr.
+int sell_lanes(int w);
+template <typename TS>
+void launch_sell_spmv(hipStream_t st, int n, int L, const long* soff, const int* sw, const int* ci, const TS* v,
+                      const double* x, double* y, double beta_y, double* zero_out = nullptr);
 // y = A x, A dense row-major n x n in storage TS with row stride ld (a
 // multiple of 4, rows zero-padded; a wavefront per row, 16-byte loads)
 template <typename TS>

@@ -169,6 +169,13 @@ struct DevTransfer {
   int *Pe_ci = nullptr, *Re_ci = nullptr;
   double *Pe_v = nullptr, *Re_v = nullptr;
   float *Pe_v32 = nullptr, *Re_v32 = nullptr;
+  // the same in sliced ELL form for the launched product (L lanes per row,
+  // slices of 64 / L rows each padded to its own width; L = 0: not built)
+  int PL = 0, RL = 0;
+  long *Ps_off = nullptr, *Rs_off = nullptr;
+  int *Ps_w = nullptr, *Rs_w = nullptr, *Ps_ci = nullptr, *Rs_ci = nullptr;
+  double *Ps_v = nullptr, *Rs_v = nullptr;
+  float *Ps_v32 = nullptr, *Rs_v32 = nullptr;
 };
 
 // CSR -> ELL (column-major, zero padding).
@@ -182,6 +189,31 @@ void to_ell(const CSR& A, int& w, std::vector<int>& ci, std::vector<double>& v) 
       ci[(size_t)(k - A.rp[r]) * A.n + r] = A.ci[k];
       v[(size_t)(k - A.rp[r]) * A.n + r] = A.v[k];
     }
+}
+
+// CSR -> sliced ELL with L lanes per row: slices of H = 64 / L rows, slice
+// s padded to its widest row, entry (slot k, row s H + rr) at
+// off[s] + k H + rr (padding: column 0, value 0).
+void to_sell(const CSR& A, int L, std::vector<long>& off, std::vector<int>& sw, std::vector<int>& ci,
+             std::vector<double>& v) {
+  const int H = 64 / L, ns = (A.n + H - 1) / H;
+  off.assign(ns + 1, 0);
+  sw.assign(std::max(ns, 1), 0);
+  for (int sl = 0; sl < ns; ++sl) {
+    int w = 0;
+    for (int r = sl * H; r < std::min(A.n, (sl + 1) * H); ++r) w = std::max(w, A.rp[r + 1] - A.rp[r]);
+    sw[sl] = w;
+    off[sl + 1] = off[sl] + (long)w * H;
+  }
+  ci.assign(std::max<long>(off[ns], 1), 0);
+  v.assign(std::max<long>(off[ns], 1), 0.0);
+  for (int r = 0; r < A.n; ++r) {
+    const int sl = r / H, rr = r - sl * H;
+    for (int k = A.rp[r]; k < A.rp[r + 1]; ++k) {
+      ci[off[sl] + (long)(k - A.rp[r]) * H + rr] = A.ci[k];
+      v[off[sl] + (long)(k - A.rp[r]) * H + rr] = A.v[k];
+    }
+  }
 }
 
 }  // namespace
@@ -931,12 +963,20 @@ void mg_h(hdgmg_ctx* ctx, int l, int m_l, bool u_zero) {
   level_apply(ctx, D, D.u, D.r, -1.0, D.g, 2, true);
   DevTransfer& T = ctx->tr[l];
   DevLevel& C = ctx->cr[l - 1];
-  if (vc_f32(ctx))
+  if (T.RL && vc_f32(ctx))
+    launch_sell_spmv<float>(ctx->st, T.ncoarse, T.RL, T.Rs_off, T.Rs_w, T.Rs_ci, T.Rs_v32, D.r, C.g, 0.0, C.u);
+  else if (T.RL)
+    launch_sell_spmv<double>(ctx->st, T.ncoarse, T.RL, T.Rs_off, T.Rs_w, T.Rs_ci, T.Rs_v, D.r, C.g, 0.0, C.u);
+  else if (vc_f32(ctx))
     launch_ell_spmv<float>(ctx->st, T.ncoarse, T.Rw, T.Re_ci, T.Re_v32, D.r, C.g, 0.0, C.u);
   else
     launch_ell_spmv<double>(ctx->st, T.ncoarse, T.Rw, T.Re_ci, T.Re_v, D.r, C.g, 0.0, C.u);  // and C.u = 0
   for (int n = 0; n < ctx->opts.cycle; ++n) mg_h(ctx, l - 1, ctx->opts.vcycle_growth * m_l, n == 0);
-  if (vc_f32(ctx))
+  if (T.PL && vc_f32(ctx))
+    launch_sell_spmv<float>(ctx->st, T.nfine, T.PL, T.Ps_off, T.Ps_w, T.Ps_ci, T.Ps_v32, C.u, D.u, 1.0);
+  else if (T.PL)
+    launch_sell_spmv<double>(ctx->st, T.nfine, T.PL, T.Ps_off, T.Ps_w, T.Ps_ci, T.Ps_v, C.u, D.u, 1.0);
+  else if (vc_f32(ctx))
     launch_ell_spmv<float>(ctx->st, T.nfine, T.Pw, T.Pe_ci, T.Pe_v32, C.u, D.u, 1.0);
   else
     launch_ell_spmv<double>(ctx->st, T.nfine, T.Pw, T.Pe_ci, T.Pe_v, C.u, D.u, 1.0);
@@ -1265,6 +1305,30 @@ hdgmg_status build_transfers(hdgmg_ctx* ctx) {
     TRY(upload(ctx, &Tt.Re_ci, eci));
     TRY(upload(ctx, &Tt.Re_v, ev));
     if (vc_f32(ctx)) TRY(upload_f32(ctx, &Tt.Re_v32, ev));
+    // sliced copies for the launched products with wide rows on large
+    // levels (below 65536 rows the extra slice-offset load costs more than
+    // the padding it saves)
+    std::vector<long> soff;
+    std::vector<int> sw;
+    constexpr int kSellRows = 65536;
+    Tt.PL = P.n >= kSellRows ? sell_lanes(Tt.Pw) : 0;
+    if (Tt.PL) {
+      to_sell(P, Tt.PL, soff, sw, eci, ev);
+      TRY(upload(ctx, &Tt.Ps_off, soff));
+      TRY(upload(ctx, &Tt.Ps_w, sw));
+      TRY(upload(ctx, &Tt.Ps_ci, eci));
+      TRY(upload(ctx, &Tt.Ps_v, ev));
+      if (vc_f32(ctx)) TRY(upload_f32(ctx, &Tt.Ps_v32, ev));
+    }
+    Tt.RL = R.n >= kSellRows ? sell_lanes(Tt.Rw) : 0;
+    if (Tt.RL) {
+      to_sell(R, Tt.RL, soff, sw, eci, ev);
+      TRY(upload(ctx, &Tt.Rs_off, soff));
+      TRY(upload(ctx, &Tt.Rs_w, sw));
+      TRY(upload(ctx, &Tt.Rs_ci, eci));
+      TRY(upload(ctx, &Tt.Rs_v, ev));
+      if (vc_f32(ctx)) TRY(upload_f32(ctx, &Tt.Rs_v32, ev));
+    }
   }
   std::vector<double> inv;
   if (!coarse_inverse(ctx->lv[0], ctx->hostB[0], general, inv)) {
