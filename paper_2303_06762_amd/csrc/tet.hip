@@ -1005,6 +1005,21 @@ __global__ void __launch_bounds__(BS) k_patch_gs3(Level3View<TS> L, const int* _
   for (int q = tid; q < ns; q += BS) {
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     int j = 0;
+    // eight columns' loads in flight per step (the same four accumulators in
+    // the same order as the four-column steps below)
+    for (; j + 8 <= ns; j += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = (double)Ai[(long)(j + u) * ns + q];
+      a0 += v[0] * res[j];
+      a1 += v[1] * res[j + 1];
+      a2 += v[2] * res[j + 2];
+      a3 += v[3] * res[j + 3];
+      a0 += v[4] * res[j + 4];
+      a1 += v[5] * res[j + 5];
+      a2 += v[6] * res[j + 6];
+      a3 += v[7] * res[j + 7];
+    }
     for (; j + 4 <= ns; j += 4) {
       const double v0 = (double)Ai[(long)j * ns + q], v1 = (double)Ai[(long)(j + 1) * ns + q];
       const double v2 = (double)Ai[(long)(j + 2) * ns + q], v3 = (double)Ai[(long)(j + 3) * ns + q];
